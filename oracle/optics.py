@@ -1,0 +1,220 @@
+"""Optics submodels of the oracle: grids, pupils, Green's spectrum, propagators.
+
+TEST INFRASTRUCTURE ONLY (see ``oracle/__init__``).
+
+Paper: Methods, "Summary of transfer functions" -- every transfer function is
+built from an illumination model (source pupil S), a scattering model (Green's
+spectrum G) and a detection model (detection pupil P), each a function on the
+spherical shell of radius 1/lambda (lambda in the medium).  Ext. Data Fig. 3
+gives the parameters: the illumination pupil depends on NA_ill and a tilt
+(zenith, azimuth) and is (Y, X); the detection pupil depends on NA_det and a
+defocus offset and is (Z, Y, X).
+
+Readings (the paper's derivations are in a supplement that is not available):
+
+R1  The shell is sampled as a 2D pupil on the lateral FFT grid times the
+    angular-spectrum propagator exp(i 2 pi kz(p) (z - dz0)), kz(p) =
+    sqrt(k_m^2 - |p|^2), k_m = n / lambda0, with signed z (forward hemisphere).
+R2  Scalar scattered arm: P(p) * g(p) with g(p) = i / cos(theta(p)),
+    cos(theta) = kz(p) / k_m -- the Weyl spectrum of the Helmholtz Green's
+    function scaled so that a laterally uniform slab of phase phi scatters
+    i*phi at normal incidence.
+R6  Pupil edge: hard disc with the boundary included, or a compact C1
+    smoothstep of half-width ``edge_width`` frequency pixels.
+R7  Tilt shifts the source disc to q0 = (n sin(zenith)/lambda0) (cos az,
+    sin az); the tilted disc must stay inside k_m.
+R8  Defocus shifts every plane, z -> z - defocus.
+All arithmetic is float64 / complex128.
+"""
+
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+
+FLUOR_3D = 0
+LABELFREE_3D = 1
+LABELFREE_THIN = 2
+POL5_3D = 3
+
+
+@dataclasses.dataclass
+class Optics:
+    """Microscope and sampling parameters of one volume or patch (units: um, rad)."""
+
+    model: int
+    nz: int
+    ny: int
+    nx: int
+    dz: float
+    dy: float
+    dx: float
+    wavelength: float          # vacuum wavelength (emission wavelength for fluorescence)
+    na_ill: float
+    na_det: float
+    n_medium: float
+    defocus: float = 0.0
+    tilt_zenith: float = 0.0
+    tilt_azimuth: float = 0.0
+    edge_width: float = 0.0    # soft pupil edge half-width in frequency pixels; 0 = hard
+    swing: float = 0.1         # polarisation bank only
+
+    def replace(self, **kw) -> "Optics":
+        return dataclasses.replace(self, **kw)
+
+    @property
+    def k_medium(self) -> float:
+        """Shell radius n / lambda0 in cycles/um (Summary of transfer functions)."""
+        return self.n_medium / self.wavelength
+
+    @property
+    def dnu(self) -> float:
+        """Lateral frequency pixel used to scale the soft pupil edge."""
+        return min(1.0 / (self.nx * self.dx), 1.0 / (self.ny * self.dy))
+
+
+def lateral_frequencies(o: Optics):
+    """(fy, fx) lateral frequency grids in cycles/um, FFT order (numpy fftfreq)."""
+    fy = np.fft.fftfreq(o.ny, o.dy)
+    fx = np.fft.fftfreq(o.nx, o.dx)
+    return np.meshgrid(fy, fx, indexing="ij")
+
+
+def z_planes_3d(o: Optics) -> np.ndarray:
+    """Axial PSF coordinates of the 3D models, FFT order: 0, dz, ..., -dz."""
+    return np.fft.fftfreq(o.nz) * o.nz * o.dz
+
+
+def z_planes_thin(o: Optics) -> np.ndarray:
+    """Physical planes of a defocus stack, centred on the nominal focus."""
+    return o.dz * (np.arange(o.nz) - (o.nz - 1) / 2.0)
+
+
+def edge(inside: np.ndarray, halfwidth: float) -> np.ndarray:
+    """Pupil edge profile of a signed distance ``inside`` (positive inside).
+
+    Hard edge (halfwidth == 0): 1 where inside >= 0, else 0.
+    Soft edge: t = clip((inside/halfwidth + 1)/2, 0, 1), value 3 t^2 - 2 t^3.
+    """
+    inside = np.asarray(inside, dtype=np.float64)
+    if halfwidth == 0.0:
+        return (inside >= 0.0).astype(np.float64)
+    t = np.clip((inside / halfwidth + 1.0) * 0.5, 0.0, 1.0)
+    return t * t * (3.0 - 2.0 * t)
+
+
+def radius_disc(fy, fx, radius: float, halfwidth: float, cy=0.0, cx=0.0):
+    """Disc of the given radius centred on (cy, cx).
+
+    The hard disc is decided on squared distances (no square root), the soft
+    disc on the signed radial distance.
+    """
+    r2 = (fy - cy) ** 2 + (fx - cx) ** 2
+    if halfwidth == 0.0:
+        return (r2 <= radius * radius).astype(np.float64)
+    return edge(radius - np.sqrt(r2), halfwidth)
+
+
+def detection_pupil(o: Optics) -> np.ndarray:
+    """P(p): disc of radius NA_det/lambda0 (Ext. Data Fig. 3b, calc_det_pupil)."""
+    fy, fx = lateral_frequencies(o)
+    return radius_disc(fy, fx, o.na_det / o.wavelength, o.edge_width * o.dnu)
+
+
+def source_centre(o: Optics):
+    """q0 = (n sin(zenith) / lambda0) (sin az, cos az) as (qy, qx) (reading R7)."""
+    r = o.n_medium * math.sin(o.tilt_zenith) / o.wavelength
+    return r * math.sin(o.tilt_azimuth), r * math.cos(o.tilt_azimuth)
+
+
+def illumination_pupil(o: Optics) -> np.ndarray:
+    """S(q): disc of radius NA_ill/lambda0 centred at the tilt q0 (calc_ill_pupil)."""
+    fy, fx = lateral_frequencies(o)
+    cy, cx = source_centre(o)
+    return radius_disc(fy, fx, o.na_ill / o.wavelength, o.edge_width * o.dnu, cy, cx)
+
+
+def axial_wavenumber(o: Optics, wavelength: float | None = None) -> np.ndarray:
+    """kz(p) = sqrt(k_m^2 - |p|^2), set to 0 outside the shell (evanescent)."""
+    lam = o.wavelength if wavelength is None else wavelength
+    km = o.n_medium / lam
+    fy, fx = lateral_frequencies(o)
+    return np.sqrt(np.maximum(km * km - fy * fy - fx * fx, 0.0))
+
+
+def greens_spectrum(o: Optics) -> np.ndarray:
+    """Scalar scattered-field factor g(p) = i / cos(theta(p)) (reading R2).
+
+    Zero where kz = 0 (the pupils vanish there, which ``check_optics`` enforces).
+    """
+    kz = axial_wavenumber(o)
+    g = np.zeros(kz.shape, dtype=np.complex128)
+    ok = kz > 0
+    g[ok] = 1j * o.k_medium / kz[ok]
+    return g
+
+
+def propagator(o: Optics, z: float) -> np.ndarray:
+    """Angular-spectrum propagator exp(i 2 pi kz(p) (z - defocus)) (readings R1, R8)."""
+    return np.exp(2j * np.pi * axial_wavenumber(o) * (z - o.defocus))
+
+
+def background(o: Optics) -> float:
+    """Direct-direct intensity I_bg = sum_q S(q) P(q)^2 (unified-framework section)."""
+    return float(np.sum(illumination_pupil(o) * detection_pupil(o) ** 2))
+
+
+def check_optics(o: Optics) -> None:
+    """Raise ValueError where the discrete model is not the paper's continuous one.
+
+    * pupils must stay strictly inside the shell (no evanescent support, where
+      the Green's factor 1/cos(theta) diverges);
+    * the label-free correlation must not wrap laterally: its support radius
+      (NA_det + NA_ill)/lambda0 + |q0| must stay below the lateral Nyquist
+      frequency; fluorescence needs 2 NA_det/lambda0 below it;
+    * the axial support must stay below the axial Nyquist frequency.
+    """
+    if min(o.nz, o.ny, o.nx) < 1 or min(o.dz, o.dy, o.dx) <= 0 or o.wavelength <= 0:
+        raise ValueError("bad sampling")
+    if o.na_det < 0 or o.na_ill < 0 or o.n_medium <= 0:
+        raise ValueError("bad aperture")
+    km = o.k_medium
+    hw = o.edge_width * o.dnu
+    if o.na_det / o.wavelength + hw >= km:
+        raise ValueError("detection pupil reaches the evanescent boundary")
+    qy, qx = source_centre(o)
+    q0 = math.hypot(qy, qx)
+    if o.model != FLUOR_3D and o.na_ill / o.wavelength + q0 + hw >= km:
+        raise ValueError("illumination pupil reaches the evanescent boundary")
+    nyq = min(0.5 / o.dx, 0.5 / o.dy)
+    if o.model == FLUOR_3D:
+        lat = 2.0 * (o.na_det / o.wavelength + hw)
+        ax = km * (1.0 - math.sqrt(1.0 - ((o.na_det / o.wavelength + hw) / km) ** 2))
+    else:
+        lat = (o.na_det + o.na_ill) / o.wavelength + q0 + 2.0 * hw
+        kd = min(o.na_det / o.wavelength + hw, km)
+        ax = km - math.sqrt(km * km - kd * kd)
+    if lat >= nyq:
+        raise ValueError("lateral aliasing")
+    if o.model != LABELFREE_THIN and ax >= 0.5 / o.dz:
+        raise ValueError("axial aliasing")
+
+
+def hard_edge_margin(o: Optics) -> float:
+    """Smallest relative distance of a lattice point's |p|^2 from a hard edge radius^2.
+
+    Used by tests to make sure FP32/FP64 evaluations of the hard disc agree.
+    """
+    fy, fx = lateral_frequencies(o)
+    out = np.inf
+    for radius, (cy, cx) in (
+        (o.na_det / o.wavelength, (0.0, 0.0)),
+        (o.na_ill / o.wavelength, source_centre(o)),
+    ):
+        if radius <= 0:
+            continue
+        r2 = (fy - cy) ** 2 + (fx - cx) ** 2
+        out = min(out, float(np.min(np.abs(r2 - radius * radius))) / (radius * radius))
+    return out
