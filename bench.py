@@ -1,0 +1,213 @@
+"""Throughput of the WaveOrder hot path on one MI355X.
+
+Workload: label-free absorption + phase from a brightfield stack,
+96 x 512 x 512 voxels (dz 0.2 um, dx = dy 0.1 um), lambda0 0.532 um, NA_ill
+0.5, NA_det 1.2, n 1.33; 1 channel -> 2 properties; 200 random ellipsoids,
+Poisson-Gaussian noise.  One step is the whole reconstruction hot path on
+that volume: transfer-function synthesis (pupils, propagators, correlation,
+3D transforms) followed by the Tikhonov reconstruction (forward 3D FFT,
+per-frequency solve fused with the Z transform, inverse 3D FFT).  Inputs are
+resident in HBM before timing starts.
+
+Prints one JSON line.  `value` = reconstructed voxels per second for the step
+above; extra fields give the rate with a cached transfer function, each
+kernel's time and algorithmic bytes, the roofline of the dominant kernel and
+the FP64 oracle timed on a bounded sample on the host.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+WORKLOAD = dict(model=1, nz=96, ny=512, nx=512, dz=0.2, dy=0.1, dx=0.1, wavelength=0.532,
+                na_ill=0.5, na_det=1.2, n_medium=1.33, defocus=0.0, tilt_zenith=0.0,
+                tilt_azimuth=0.0, edge_width=0.0, swing=0.1)
+ETA_REL = 1e-3
+
+
+def kernel_bytes(name, Z, Y, X, C=1, P=2):
+    """Algorithmic HBM bytes one launch of each kernel must move in this step."""
+    Xh = X // 2 + 1
+    cplx = 8
+    half = Z * Y * Xh
+    full = Z * Y * X
+    table = {
+        # reconstruction
+        "k_rows_r2c": C * (4 * full + cplx * half),
+        "k_cols_y_fwd": C * 2 * cplx * half,
+        f"k_zop<{P}>": cplx * half * (C + C * P + P),
+        "k_cols_y_inv": P * 2 * cplx * half,
+        "k_rows_c2r": P * (cplx * half + 4 * full),
+        # transfer-function synthesis
+        "k_pupil_sums": 0,
+        "k_tf_fields_y": 2 * cplx * full,
+        "k_tf_rows_lf": 2 * cplx * full + 2 * cplx * half,
+        "k_cols_y_tf": 2 * 2 * cplx * half,
+        "k_cols_z_tf": 2 * 2 * cplx * half,
+    }
+    return table.get(name)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-nz", type=int, default=24)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus above 1 is not supported"}))
+        sys.exit(2)
+
+    import torch
+
+    import synth
+    from paper_2412_09775_amd import api
+
+    api.load()
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    o = api.Optics(**WORKLOAD)
+    Z, Y, X = o.nz, o.ny, o.nx
+    V = Z * Y * X
+
+    # ---- inputs (untimed): specimen, forward model on the GPU, noise on the host
+    t0 = time.time()
+    obj = synth.ellipsoids((Z, Y, X), (o.dz, o.dy, o.dx), 200, seed=2001)
+    print(f"[bench] specimen generated in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+    tf = api.transfer_function([o], device=dev)
+    clean = api.forward([o], tf, torch.from_numpy(obj[None]).to(dev))
+    noisy = synth.poisson_gaussian(clean.cpu().numpy(), seed=2002)
+    d = torch.from_numpy(noisy).to(dev)
+    # eta relative to the largest |H|^2 (1 channel: sigma_max^2 = |H_phase|^2 + |H_abs|^2)
+    smax2 = float((tf.abs() ** 2).sum(dim=2).max())
+    eta = ETA_REL * smax2
+    ws_tf = torch.empty(api.workspace_size([o], api.OP_TRANSFER_FUNCTION), dtype=torch.uint8, device=dev)
+    ws_rec = torch.empty(api.workspace_size([o], api.OP_RECONSTRUCT), dtype=torch.uint8, device=dev)
+    tf_buf = torch.empty_like(tf)
+    lib = api.load()
+    arr = api.optics_array([o])
+    fout = torch.empty((1, 2, Z, Y, X), dtype=torch.float32, device=dev)
+    stream = torch.cuda.current_stream()
+    sp = api._stream(stream)
+
+    def step_tf():
+        st = lib.wo_transfer_function(arr, 1, api._ptr(tf_buf), api._ptr(ws_tf), ws_tf.numel(), sp)
+        assert st == 0, st
+
+    def step_rec(bank):
+        st = lib.wo_reconstruct(arr, 1, api._ptr(bank), api._ptr(d), None, eta, api._ptr(fout),
+                                api._ptr(ws_rec), ws_rec.numel(), sp)
+        assert st == 0, st
+
+    def full_step():
+        step_tf()
+        step_rec(tf_buf)
+
+    for _ in range(args.warmup):
+        full_step()
+    torch.cuda.synchronize()
+    print("[bench] warmup done", file=sys.stderr, flush=True)
+
+    # ---- timed region: K whole steps, with per-kernel HIP events on the library's stream
+    api.timing_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        full_step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    api.timing_enable(False)
+    kern = api.timing_report()
+    ms = (t1 - t0) * 1e3 / args.steps
+    value = V / (ms * 1e-3)
+
+    # ---- cached-TF reconstruction rate (secondary)
+    torch.cuda.synchronize()
+    r0 = time.perf_counter()
+    for _ in range(args.steps):
+        step_rec(tf_buf)
+    torch.cuda.synchronize()
+    ms_rec = (time.perf_counter() - r0) * 1e3 / args.steps
+
+    kernels = {}
+    for name, (cnt, tot) in sorted(kern.items()):
+        per = tot / cnt
+        b = kernel_bytes(name, Z, Y, X)
+        ent = {"launches": cnt, "avg_ms": round(per, 5)}
+        if b:
+            ent["alg_bytes"] = b
+            ent["alg_GBps"] = round(b / (per * 1e-3) / 1e9, 1)
+        kernels[name] = ent
+    dom = max(kern, key=lambda k: kern[k][1])
+    dom_b = kernel_bytes(dom, Z, Y, X) or 0
+    dom_ms = kern[dom][1] / kern[dom][0]
+    ach = dom_b / (dom_ms * 1e-3) / 1e9
+    roof = {"kernel": dom, "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None}
+
+    out = {
+        "metric": "reconstructed voxels/s (TF synthesis + Tikhonov reconstruction per step)",
+        "value": value,
+        "unit": "voxels/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "label-free 3D phase+absorption, 96x512x512, 1 channel x 2 properties",
+                   "shape_zyx": [Z, Y, X], "voxel_um": [o.dz, o.dy, o.dx], "eta_rel": ETA_REL},
+        "reconstruct_cached_tf": {"ms": ms_rec, "voxels_per_s": V / (ms_rec * 1e-3)},
+        "roofline": roof,
+        "kernels": kernels,
+    }
+
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(o, args.cpu_sample_nz)
+    print(json.dumps(out))
+
+
+def cpu_baseline(o, nz):
+    """FP64 oracle (TF synthesis + reconstruction) on a bounded slab of the workload."""
+    import scipy.fft as sfft
+
+    import synth
+    from oracle import linear
+    from oracle import optics as op
+    from oracle import tf as tfm
+
+    cores = len(os.sched_getaffinity(0))
+    oo = op.Optics(model=op.LABELFREE_3D, nz=nz, ny=o.ny, nx=o.nx, dz=o.dz, dy=o.dy, dx=o.dx,
+                   wavelength=o.wavelength, na_ill=o.na_ill, na_det=o.na_det, n_medium=o.n_medium)
+    data = synth.gaussian_noise((1, nz, o.ny, o.nx), 1e-2, 77)
+    t0 = time.perf_counter()
+    with sfft.set_workers(cores):
+        bank = tfm.transfer_function(oo)
+        t1 = time.perf_counter()
+        eta = ETA_REL * linear.max_singular_value_sq(bank)
+        linear.reconstruct(bank, data, None, eta)
+    t2 = time.perf_counter()
+    vox = nz * o.ny * o.nx
+    return {"value": vox / (t2 - t0), "unit": "voxels/s", "cores": cores, "kind": "oracle",
+            "sample": f"one {nz}x{o.ny}x{o.nx} slab of the workload (TF synthesis + reconstruction, FP64)",
+            "seconds": round(t2 - t0, 2), "tf_seconds": round(t1 - t0, 2)}
+
+
+if __name__ == "__main__":
+    main()

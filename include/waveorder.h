@@ -1,0 +1,158 @@
+/*
+ * waveorder.h -- C ABI of the MI355X (gfx950) WaveOrder hot path.
+ *
+ * WaveOrder (arXiv 2412.09775) models an imaging system as d = H f + b
+ * (Methods, "Imaging and reconstruction as linear operators", Eq. fwd) with a
+ * bank of shift-invariant transfer functions H_cp, one per data channel c and
+ * object property p (Methods, "Linear contrast-separable shift-invariant
+ * imaging systems"), built from an illumination pupil S, a scattering model G
+ * and a detection pupil P (Methods, "Summary of transfer functions"; Table 1),
+ * and reconstructs f by a Tikhonov-regularised least-squares solve
+ * (Methods, "Reconstructing object properties" and "Reconstruction
+ * algorithm", Eq. tls_solution).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  * All array pointers are DEVICE pointers owned by the caller.  The library
+ *    never allocates device memory: scratch space comes from `ws`, whose size
+ *    wo_workspace_size() gives.  Nothing is freed by the library.
+ *  * Calls are asynchronous on `stream` (a hipStream_t, NULL = default
+ *    stream); arguments are validated synchronously before anything is
+ *    enqueued, and an error leaves the outputs untouched.  The optics array
+ *    `o` is host memory and is read (and copied into `ws`) during the call.
+ *  * A call processes `n` patches that share the sampling (model, nz, ny, nx,
+ *    dz, dy, dx) but may differ in every optical parameter.  Patch i of an
+ *    array argument follows patch i-1 contiguously.
+ *  * Volumes are float32, C-contiguous [Z][Y][X] with X fastest.  Channel and
+ *    property maps of one patch are stacked in front: [C][Z][Y][X].
+ *  * Spectra and transfer functions are complex64 (interleaved re, im) on the
+ *    half spectrum along X: kx = 0..X/2, so Xh = X/2 + 1 values per row; ky
+ *    and kz are in FFT order (DC first).  The full spectrum is the Hermitian
+ *    extension H(-nu) = conj(H(nu)) (transfer functions of real data are
+ *    Hermitian, Methods "Summary of transfer functions").
+ *  * Sizes nz, ny, nx must factor into 2, 3 and 5 and lie in [1, 4096] (ny, nx
+ *    even); otherwise WO_EUNSUPPORTED.
+ *  * Units: lengths in micrometres, angles in radians.  Label-free properties
+ *    are radians per voxel (phase 2 pi dn dz / lambda0, absorption
+ *    2 pi dkappa dz / lambda0); label-free data are the relative contrast
+ *    I / I_bg - 1.
+ *
+ * Models (WO_MODEL_*), bank shape C x P and spatial dimensions:
+ *   FLUOR_3D        1 x 1, 3D  scalar fluorescence OTF [P * P], H(0) = 1
+ *   LABELFREE_3D    1 x 2, 3D  scalar label-free [phase, absorption]
+ *   LABELFREE_THIN  nz x 2, 2D phase from a defocus stack: channel k is the
+ *                   plane at z_k = dz (k - (nz-1)/2); properties are a thin
+ *                   object [phase, absorption] of shape [Y][X]
+ *   POL5_3D         5 x 4, 3D  five polarisation states (swing) through a
+ *                   circular analyser; properties [phase, rho cos 2w,
+ *                   rho sin 2w, absorption]
+ */
+#ifndef WAVEORDER_H
+#define WAVEORDER_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  WO_OK = 0,
+  WO_EINVAL = -1,        /* bad argument or optics outside the model's validity */
+  WO_EUNSUPPORTED = -2,  /* size or mode the kernels do not implement */
+  WO_ENOMEM = -3,        /* workspace smaller than wo_workspace_size() */
+  WO_EHIP = -4,          /* the HIP runtime reported an error */
+  WO_EALIAS = -5         /* transfer-function support exceeds the sampled band */
+};
+
+enum {
+  WO_MODEL_FLUOR_3D = 0,
+  WO_MODEL_LABELFREE_3D = 1,
+  WO_MODEL_LABELFREE_THIN = 2,
+  WO_MODEL_POL5_3D = 3
+};
+
+enum {
+  WO_OP_TRANSFER_FUNCTION = 0,
+  WO_OP_FORWARD = 1,
+  WO_OP_RECONSTRUCT = 2,
+  WO_OP_ADJOINT = 3
+};
+
+/* Optics and sampling of one patch (Ext. Data Fig. 3: calc_ill_pupil takes
+ * NA_ill and the tilt; calc_det_pupil takes NA_det and the defocus offset). */
+typedef struct wo_optics {
+  int32_t model;           /* WO_MODEL_* */
+  int32_t nz, ny, nx;      /* volume shape */
+  double dz, dy, dx;       /* voxel size, um */
+  double wavelength;       /* vacuum wavelength lambda0, um (emission for fluorescence) */
+  double na_ill;           /* illumination NA (ignored for fluorescence) */
+  double na_det;           /* detection NA */
+  double n_medium;         /* refractive index of the medium; the pupils live on the
+                              shell of radius n / lambda0 */
+  double defocus;          /* focal-plane offset dz0, um: every plane z -> z - dz0 */
+  double tilt_zenith;      /* illumination tilt: source disc centred at */
+  double tilt_azimuth;     /*   (n sin(zenith)/lambda0)(cos az, sin az) in (x, y) */
+  double edge_width;       /* pupil edge: 0 = hard disc (boundary included); w > 0 =
+                              C1 smoothstep of half-width w lateral frequency pixels */
+  double swing;            /* POL5_3D only: retarder swing in waves */
+} wo_optics;
+
+/* Bank shape of the model: *C channels, *P properties, *dims spatial
+ * dimensions (3 or 2); *bank_elems complex64 values per patch
+ * (C*P*nz*ny*Xh for 3D models, C*P*ny*Xh for the thin model). */
+int wo_bank_shape(const wo_optics* o, int32_t* C, int32_t* P, int32_t* dims, int64_t* bank_elems);
+
+/* Workspace bytes an operation (WO_OP_*) needs for n patches of this sampling. */
+size_t wo_workspace_size(const wo_optics* o, int32_t n, int32_t op);
+
+/* Transfer-function bank (Table 1, scalar column; the polarisation bank is
+ * the paraxial Jones reduction H_cp = Re(kappa_cp) H_phase + Im(kappa_cp) H_abs).
+ * tf_out: complex64 [n][C][P][nz][ny][Xh] (3D) or [n][nz][2][ny][Xh] (thin).
+ * WO_EINVAL if a pupil reaches the evanescent boundary n/lambda0 or an NA,
+ * size or wavelength is not positive; WO_EALIAS if the lateral support
+ * exceeds the lateral Nyquist frequency or the axial support the axial one. */
+int wo_transfer_function(const wo_optics* o, int32_t n, void* tf_out, void* ws, size_t ws_bytes,
+                         void* stream);
+
+/* Forward model D_c = sum_p H_cp F_p + N b_c delta(nu), d_c = IFFT(D_c)
+ * (Methods, "Linear contrast-separable shift-invariant imaging systems").
+ * tf: bank from wo_transfer_function (or any Hermitian bank of that layout);
+ * f: [n][P][vol], b: [n][C] or NULL, d_out: [n][C][vol]; vol = nz*ny*nx
+ * (3D) or ny*nx for the thin model's object. */
+int wo_forward(const wo_optics* o, int32_t n, const void* tf, const float* f, const float* b,
+               float* d_out, void* ws, size_t ws_bytes, void* stream);
+
+/* Tikhonov reconstruction f = argmin ||d - b - H f||^2 + eta ||f||^2, solved
+ * per spatial frequency as F = (H^H H + eta I)^-1 H^H (D - N b delta)
+ * (Eq. recon and Eq. tls_solution).  d: [n][C][vol], b: [n][C] or NULL,
+ * f_out: [n][P][vol] (thin: [n][2][ny][nx]).  eta >= 0 (absolute); eta == 0
+ * is supported for P == 1 only (F = 0 where H = 0), else WO_EUNSUPPORTED. */
+int wo_reconstruct(const wo_optics* o, int32_t n, const void* tf, const float* d, const float* b,
+                   double eta, float* f_out, void* ws, size_t ws_bytes, void* stream);
+
+/* Adjoint g_p = IFFT(sum_c conj(H_cp) R_c): r [n][C][vol] -> g_out [n][P][vol]. */
+int wo_adjoint(const wo_optics* o, int32_t n, const void* tf, const float* r, float* g_out,
+               void* ws, size_t ws_bytes, void* stream);
+
+/* Instrumentation (not part of the method): while enabled, every kernel the
+ * library launches is bracketed by HIP events on the stream it runs on.
+ * wo_timing_report() waits for the recorded events, writes one line
+ * "<kernel> <launches> <total_ms>" per kernel name into buf (NUL-terminated,
+ * truncated to len), and clears the records.  Returns WO_EHIP if an event
+ * failed. */
+int wo_timing_enable(int on);
+int wo_timing_report(char* buf, size_t len);
+
+/* Human-readable message for a status code. */
+const char* wo_strerror(int status);
+
+/* ABI version of this header (major * 100 + minor). */
+int wo_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* WAVEORDER_H */

@@ -1,0 +1,245 @@
+"""Thin Python binding of ``libwaveorder.so`` (argument marshalling only).
+
+Every step of the hot path runs in the HIP kernels behind the C ABI declared
+in ``include/waveorder.h``.  PyTorch only provides device memory (tensors)
+and the current HIP stream.  There is no CPU fallback: if the library is
+missing, :func:`load` raises.
+
+Optics are passed as any object (or dict) with the fields of ``wo_optics``:
+model, nz, ny, nx, dz, dy, dx, wavelength, na_ill, na_det, n_medium, defocus,
+tilt_zenith, tilt_azimuth, edge_width, swing.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libwaveorder.so")
+
+MODEL_FLUOR_3D = 0
+MODEL_LABELFREE_3D = 1
+MODEL_LABELFREE_THIN = 2
+MODEL_POL5_3D = 3
+
+OP_TRANSFER_FUNCTION = 0
+OP_FORWARD = 1
+OP_RECONSTRUCT = 2
+OP_ADJOINT = 3
+
+SYMBOLS = ("wo_bank_shape", "wo_workspace_size", "wo_transfer_function", "wo_forward",
+           "wo_reconstruct", "wo_adjoint", "wo_strerror", "wo_version", "wo_timing_enable",
+           "wo_timing_report")
+
+_FIELDS = ("model", "nz", "ny", "nx", "dz", "dy", "dx", "wavelength", "na_ill", "na_det",
+           "n_medium", "defocus", "tilt_zenith", "tilt_azimuth", "edge_width", "swing")
+
+
+class WoOptics(ctypes.Structure):
+    _fields_ = [("model", ctypes.c_int32), ("nz", ctypes.c_int32), ("ny", ctypes.c_int32),
+                ("nx", ctypes.c_int32)] + [(f, ctypes.c_double) for f in _FIELDS[4:]]
+
+
+@dataclasses.dataclass
+class Optics:
+    """Python mirror of ``wo_optics``."""
+
+    model: int
+    nz: int
+    ny: int
+    nx: int
+    dz: float
+    dy: float
+    dx: float
+    wavelength: float
+    na_ill: float
+    na_det: float
+    n_medium: float
+    defocus: float = 0.0
+    tilt_zenith: float = 0.0
+    tilt_azimuth: float = 0.0
+    edge_width: float = 0.0
+    swing: float = 0.1
+
+
+class WoError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        msg = _lib.wo_strerror(status).decode() if _lib is not None else str(status)
+        super().__init__(f"{where}: {msg} (status {status})")
+        self.status = status
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load the HIP library (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with paper_2412_09775_amd.build.build()")
+    lib = ctypes.CDLL(path)
+    vp, sz, i32 = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int32
+    op = ctypes.POINTER(WoOptics)
+    lib.wo_bank_shape.argtypes = [op, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32),
+                                  ctypes.POINTER(ctypes.c_int64)]
+    lib.wo_workspace_size.argtypes = [op, i32, i32]
+    lib.wo_workspace_size.restype = sz
+    lib.wo_transfer_function.argtypes = [op, i32, vp, vp, sz, vp]
+    lib.wo_forward.argtypes = [op, i32, vp, vp, vp, vp, vp, sz, vp]
+    lib.wo_reconstruct.argtypes = [op, i32, vp, vp, vp, ctypes.c_double, vp, vp, sz, vp]
+    lib.wo_adjoint.argtypes = [op, i32, vp, vp, vp, vp, sz, vp]
+    lib.wo_strerror.argtypes = [ctypes.c_int]
+    lib.wo_strerror.restype = ctypes.c_char_p
+    lib.wo_version.restype = ctypes.c_int
+    lib.wo_timing_enable.argtypes = [ctypes.c_int]
+    lib.wo_timing_report.argtypes = [ctypes.c_char_p, ctypes.c_size_t]
+    for name in SYMBOLS:
+        getattr(lib, name)
+    _lib = lib
+    return lib
+
+
+def _get(o, name):
+    return o[name] if isinstance(o, dict) else getattr(o, name)
+
+
+def optics_array(optics) -> ctypes.Array:
+    """ctypes array of wo_optics from one optics object or a sequence of them."""
+    if not isinstance(optics, (list, tuple)):
+        optics = [optics]
+    arr = (WoOptics * len(optics))()
+    for i, o in enumerate(optics):
+        for f in _FIELDS:
+            setattr(arr[i], f, int(_get(o, f)) if f in ("model", "nz", "ny", "nx") else float(_get(o, f)))
+    return arr
+
+
+def _check(status: int, where: str):
+    if status != 0:
+        raise WoError(status, where)
+
+
+def bank_shape(optics):
+    """(C, P, dims, complex elements per patch) of the model's bank."""
+    lib = load()
+    arr = optics_array(optics)
+    C, P, dims = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    n = ctypes.c_int64()
+    _check(lib.wo_bank_shape(arr, ctypes.byref(C), ctypes.byref(P), ctypes.byref(dims), ctypes.byref(n)),
+           "wo_bank_shape")
+    return C.value, P.value, dims.value, n.value
+
+
+def workspace_size(optics, op: int) -> int:
+    lib = load()
+    arr = optics_array(optics)
+    return int(lib.wo_workspace_size(arr, len(arr), op))
+
+
+def _stream(stream):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _workspace(optics, op, device, ws=None):
+    import torch
+    need = workspace_size(optics, op)
+    if ws is not None and ws.numel() >= need:
+        return ws, need
+    return torch.empty(max(need, 1), dtype=torch.uint8, device=device), need
+
+
+def bank_dims(optics):
+    """Tensor shape of one call's bank: (n, C, P, [Z,] Y, X/2+1)."""
+    arr = optics_array(optics)
+    o = arr[0]
+    C, P, dims, _ = bank_shape(optics)
+    xh = o.nx // 2 + 1
+    if dims == 3:
+        return (len(arr), C, P, o.nz, o.ny, xh)
+    return (len(arr), C, P, o.ny, xh)
+
+
+def transfer_function(optics, device="cuda", out=None, ws=None, stream=None):
+    """TF bank (complex64) for one or more patches; see ``wo_transfer_function``."""
+    import torch
+    lib = load()
+    arr = optics_array(optics)
+    shape = bank_dims(optics)
+    if out is None:
+        out = torch.empty(shape, dtype=torch.complex64, device=device)
+    ws, need = _workspace(optics, OP_TRANSFER_FUNCTION, out.device, ws)
+    _check(lib.wo_transfer_function(arr, len(arr), _ptr(out), _ptr(ws), ws.numel(), _stream(stream)),
+           "wo_transfer_function")
+    return out
+
+
+def _linear(fn, name, optics, tf, x, out_shape, extra, ws, stream, op):
+    import torch
+    lib = load()
+    arr = optics_array(optics)
+    out = torch.empty(out_shape, dtype=torch.float32, device=x.device)
+    ws, _ = _workspace(optics, op, x.device, ws)
+    _check(fn(arr, len(arr), _ptr(tf), _ptr(x), *extra(out), _ptr(ws), ws.numel(), _stream(stream)), name)
+    return out
+
+
+def _vol(optics):
+    o = optics_array(optics)[0]
+    return (o.ny, o.nx) if o.model == MODEL_LABELFREE_THIN else (o.nz, o.ny, o.nx)
+
+
+def forward(optics, tf, f, b=None, ws=None, stream=None):
+    """d = H f + b; f: (n, P, *vol) float32 -> d: (n, C, *dvol)."""
+    arr = optics_array(optics)
+    C, P, dims, _ = bank_shape(optics)
+    o = arr[0]
+    dshape = (len(arr), C, o.ny, o.nx) if dims == 2 else (len(arr), C, o.nz, o.ny, o.nx)
+    lib = load()
+    return _linear(lib.wo_forward, "wo_forward", optics, tf, f.contiguous(), dshape,
+                   lambda out: (_ptr(b), _ptr(out)), ws, stream, OP_FORWARD)
+
+
+def reconstruct(optics, tf, d, eta, b=None, ws=None, stream=None):
+    """Tikhonov reconstruction; d: (n, C, *dvol) -> f: (n, P, *vol)."""
+    arr = optics_array(optics)
+    C, P, dims, _ = bank_shape(optics)
+    fshape = (len(arr), P) + _vol(optics)
+    lib = load()
+    return _linear(lib.wo_reconstruct, "wo_reconstruct", optics, tf, d.contiguous(), fshape,
+                   lambda out: (_ptr(b), ctypes.c_double(eta), _ptr(out)), ws, stream, OP_RECONSTRUCT)
+
+
+def adjoint(optics, tf, r, ws=None, stream=None):
+    """g = H^H r; r: (n, C, *dvol) -> g: (n, P, *vol)."""
+    arr = optics_array(optics)
+    C, P, dims, _ = bank_shape(optics)
+    gshape = (len(arr), P) + _vol(optics)
+    lib = load()
+    return _linear(lib.wo_adjoint, "wo_adjoint", optics, tf, r.contiguous(), gshape,
+                   lambda out: (_ptr(out),), ws, stream, OP_ADJOINT)
+
+
+def timing_enable(on: bool = True):
+    """Bracket every library kernel launch with HIP events (instrumentation)."""
+    load().wo_timing_enable(1 if on else 0)
+
+
+def timing_report() -> dict:
+    """{kernel: (launches, total_ms)} since the last report; waits for the events."""
+    buf = ctypes.create_string_buffer(1 << 16)
+    _check(load().wo_timing_report(buf, len(buf)), "wo_timing_report")
+    out = {}
+    for line in buf.value.decode().splitlines():
+        name, cnt, ms = line.split()
+        out[name] = (int(cnt), float(ms))
+    return out

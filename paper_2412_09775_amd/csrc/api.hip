@@ -1,0 +1,466 @@
+// C ABI: validation, workspace layout and the launch sequence of each call.
+#include <math.h>
+#include <string.h>
+
+#include <complex>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/waveorder.h"
+#include "internal.hpp"
+
+using namespace wo;
+
+namespace wo {
+
+long lds_limit_bytes() {
+  static long cached = 0;
+  if (cached == 0) {
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess &&
+        v > 0)
+      cached = v;
+    else
+      cached = 65536;
+  }
+  return cached;
+}
+
+// ---------------------------------------------------------------- timing
+
+namespace {
+struct TimingRec {
+  const char* name;
+  hipEvent_t a, b;
+};
+std::mutex g_tmu;
+bool g_timing = false;
+std::vector<TimingRec> g_recs;
+std::vector<hipEvent_t> g_pool;
+
+hipEvent_t take_event() {
+  if (!g_pool.empty()) {
+    hipEvent_t e = g_pool.back();
+    g_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+}  // namespace
+
+bool timing_enabled() { return g_timing; }
+
+void timing_begin(const char* name, hipStream_t s, void** token) {
+  std::lock_guard<std::mutex> lk(g_tmu);
+  TimingRec* r = new TimingRec{name, take_event(), take_event()};
+  if (!r->a || !r->b) {
+    delete r;
+    *token = nullptr;
+    return;
+  }
+  hipEventRecord(r->a, s);
+  *token = r;
+}
+
+void timing_end(void* token, hipStream_t s) {
+  TimingRec* r = (TimingRec*)token;
+  hipEventRecord(r->b, s);
+  std::lock_guard<std::mutex> lk(g_tmu);
+  g_recs.push_back(*r);
+  delete r;
+}
+
+}  // namespace wo
+
+namespace {
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+bool smooth235(int n) {
+  if (n < 1 || n > 4096) return false;
+  for (int f : {2, 3, 5})
+    while (n % f == 0) n /= f;
+  return n == 1;
+}
+
+struct Shape {
+  int C, P, dims;
+  bool thin;
+  long Z, Y, X, Xh;
+};
+
+bool bank_shape(const wo_optics* o, Shape* s) {
+  s->Z = o->nz;
+  s->Y = o->ny;
+  s->X = o->nx;
+  s->Xh = o->nx / 2 + 1;
+  s->thin = false;
+  s->dims = 3;
+  switch (o->model) {
+    case WO_MODEL_FLUOR_3D: s->C = 1; s->P = 1; break;
+    case WO_MODEL_LABELFREE_3D: s->C = 1; s->P = 2; break;
+    case WO_MODEL_LABELFREE_THIN: s->C = o->nz; s->P = 2; s->thin = true; s->dims = 2; break;
+    case WO_MODEL_POL5_3D: s->C = 5; s->P = 4; break;
+    default: return false;
+  }
+  return true;
+}
+
+long bank_elems(const Shape& s) {
+  return s.thin ? (long)s.C * s.P * s.Y * s.Xh : (long)s.C * s.P * s.Z * s.Y * s.Xh;
+}
+
+int check_sampling(const wo_optics* o) {
+  if (!o) return WO_EINVAL;
+  if (o->model < 0 || o->model > 3) return WO_EINVAL;
+  if (!(o->dz > 0 && o->dy > 0 && o->dx > 0 && o->wavelength > 0)) return WO_EINVAL;
+  if (!smooth235(o->nz) || !smooth235(o->ny) || !smooth235(o->nx)) return WO_EUNSUPPORTED;
+  if (o->nx % 2 || o->ny % 2) return WO_EUNSUPPORTED;
+  if (o->model == WO_MODEL_LABELFREE_THIN && o->nz > 64) return WO_EUNSUPPORTED;
+  return WO_OK;
+}
+
+bool same_sampling(const wo_optics* a, const wo_optics* b) {
+  return a->model == b->model && a->nz == b->nz && a->ny == b->ny && a->nx == b->nx &&
+         a->dz == b->dz && a->dy == b->dy && a->dx == b->dx;
+}
+
+// Validity of the sampled model (same conditions as the FP64 oracle).
+int check_optics(const wo_optics* o) {
+  if (!(o->na_det >= 0 && o->na_ill >= 0 && o->n_medium > 0 && o->edge_width >= 0))
+    return WO_EINVAL;
+  if (!(isfinite(o->defocus) && isfinite(o->tilt_zenith) && isfinite(o->tilt_azimuth)))
+    return WO_EINVAL;
+  const double km = o->n_medium / o->wavelength;
+  const double dnu = fmin(1.0 / (o->nx * o->dx), 1.0 / (o->ny * o->dy));
+  const double hw = o->edge_width * dnu;
+  if (o->na_det / o->wavelength + hw >= km) return WO_EINVAL;
+  const double q0 = fabs(o->n_medium * sin(o->tilt_zenith) / o->wavelength);
+  if (o->model != WO_MODEL_FLUOR_3D && o->na_ill / o->wavelength + q0 + hw >= km) return WO_EINVAL;
+  const double nyq = fmin(0.5 / o->dx, 0.5 / o->dy);
+  double lat, ax;
+  const double kd = fmin(o->na_det / o->wavelength + hw, km);
+  if (o->model == WO_MODEL_FLUOR_3D) {
+    lat = 2.0 * (o->na_det / o->wavelength + hw);
+  } else {
+    lat = (o->na_det + o->na_ill) / o->wavelength + q0 + 2.0 * hw;
+  }
+  ax = km - sqrt(km * km - kd * kd);
+  if (lat >= nyq) return WO_EALIAS;
+  if (o->model != WO_MODEL_LABELFREE_THIN && ax >= 0.5 / o->dz) return WO_EALIAS;
+  if (o->model == WO_MODEL_POL5_3D && !(isfinite(o->swing))) return WO_EINVAL;
+  return WO_OK;
+}
+
+int validate(const wo_optics* o, int32_t n) {
+  if (!o || n < 1) return WO_EINVAL;
+  int st = check_sampling(&o[0]);
+  if (st) return st;
+  for (int i = 0; i < n; ++i) {
+    if (!same_sampling(&o[0], &o[i])) return WO_EINVAL;
+    st = check_optics(&o[i]);
+    if (st) return st;
+  }
+  return WO_OK;
+}
+
+// Polarisation coupling kappa_cp = conj(a^H e_c) (a^H B_p e_c), FP64 on the host.
+void pol5_kappa(double swing, double out[5][4][2]) {
+  typedef std::complex<double> cd;
+  const double r2 = 1.0 / sqrt(2.0);
+  const cd I(0.0, 1.0);
+  cd e0[2] = {cd(r2, 0), cd(0, r2)};
+  cd states[5][2];
+  states[0][0] = e0[0];
+  states[0][1] = e0[1];
+  const double delta = 2.0 * M_PI * swing;
+  const double alphas[4] = {0.0, M_PI / 4, M_PI / 2, 3 * M_PI / 4};
+  for (int s = 0; s < 4; ++s) {
+    const double c = cos(alphas[s]), sn = sin(alphas[s]);
+    // R(a) = [[c, s], [-s, c]]; J = R(-a) diag(e^{-i d/2}, e^{i d/2}) R(a)
+    cd v0 = c * e0[0] + sn * e0[1];
+    cd v1 = -sn * e0[0] + c * e0[1];
+    v0 *= std::exp(-0.5 * I * delta);
+    v1 *= std::exp(0.5 * I * delta);
+    states[s + 1][0] = c * v0 - sn * v1;
+    states[s + 1][1] = sn * v0 + c * v1;
+  }
+  const cd ah[2] = {cd(r2, 0), cd(0, r2)};  // a^H for a = (1, -i)/sqrt2
+  const cd B[4][2][2] = {
+      {{1.0, 0.0}, {0.0, 1.0}},
+      {{0.5, 0.0}, {0.0, -0.5}},
+      {{0.0, 0.5}, {0.5, 0.0}},
+      {{I, 0.0}, {0.0, I}},
+  };
+  for (int c = 0; c < 5; ++c) {
+    const cd direct = ah[0] * states[c][0] + ah[1] * states[c][1];
+    for (int p = 0; p < 4; ++p) {
+      const cd be0 = B[p][0][0] * states[c][0] + B[p][0][1] * states[c][1];
+      const cd be1 = B[p][1][0] * states[c][0] + B[p][1][1] * states[c][1];
+      const cd k = std::conj(direct) * (ah[0] * be0 + ah[1] * be1);
+      out[c][p][0] = k.real();
+      out[c][p][1] = k.imag();
+    }
+  }
+}
+
+Sampling sampling_of(const wo_optics* o) {
+  Sampling s;
+  s.model = o->model;
+  s.nz = o->nz;
+  s.ny = o->ny;
+  s.nx = o->nx;
+  s.dz = o->dz;
+  s.dy = o->dy;
+  s.dx = o->dx;
+  return s;
+}
+
+size_t params_bytes(int32_t n) { return align_up((size_t)n * sizeof(DevOptics)); }
+
+size_t tf_ws(const wo_optics* o, int32_t n, const Shape& s) {
+  const int nf = o->model == WO_MODEL_FLUOR_3D ? 1 : 2;
+  size_t b = params_bytes(n);
+  b += align_up((size_t)n * nf * s.Z * s.Y * s.X * sizeof(float2));
+  if (o->model == WO_MODEL_POL5_3D) b += align_up((size_t)n * 2 * s.Z * s.Y * s.Xh * sizeof(float2));
+  return b;
+}
+
+size_t linear_ws(int32_t n, const Shape& s) {
+  const int CH = s.C > s.P ? s.C : s.P;
+  const long zd = s.thin ? 1 : s.Z;
+  return align_up((size_t)n * CH * zd * s.Y * s.Xh * sizeof(float2));
+}
+
+#define WO_TRY(expr)                         \
+  do {                                       \
+    hipError_t _e = (expr);                  \
+    if (_e != hipSuccess) return WO_EHIP;    \
+  } while (0)
+
+// The FFT / operator / inverse-FFT sequence shared by forward, reconstruct and adjoint.
+int run_linear(const wo_optics* o, int32_t n, const Shape& s, const float2* tf, const float* in,
+               float* out, const float* bg, int mode, float eta, void* ws, hipStream_t st) {
+  const int cin = mode == kModeForward ? s.P : s.C;
+  const int cout = mode == kModeForward ? s.C : s.P;
+  const int CH = cin > cout ? cin : cout;
+  const long zd = s.thin ? 1 : s.Z;
+  float2* spec = (float2*)ws;
+  const long M = s.Y * s.Xh;
+  RowGroups gin{cin * zd * s.Y, cin * zd * s.Y, CH * zd * s.Y, n};
+  WO_TRY(launch_rows_r2c(in, spec, (int)s.X, gin, st));
+  WO_TRY(launch_cols(spec, (int)s.Y, s.Xh, cin * zd, CH * zd, n, -1.f, st, "k_cols_y_fwd"));
+  const double nfull = s.thin ? (double)s.Y * s.X : (double)s.Z * s.Y * s.X;
+  const float inv_n = (float)(1.0 / nfull);
+  if (s.thin) {
+    WO_TRY(launch_op2d(spec, tf, s.C, s.P, M, CH, n, mode, eta, bg, inv_n, nfull, st));
+  } else {
+    WO_TRY(launch_zop(spec, tf, s.C, s.P, (int)s.Z, M, CH, n, mode, eta, bg, inv_n, nfull, st));
+  }
+  WO_TRY(launch_cols(spec, (int)s.Y, s.Xh, cout * zd, CH * zd, n, 1.f, st, "k_cols_y_inv"));
+  RowGroups gout{cout * zd * s.Y, CH * zd * s.Y, cout * zd * s.Y, n};
+  WO_TRY(launch_rows_c2r(spec, out, (int)s.X, gout, 1.f, st));
+  (void)o;
+  return WO_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int wo_version(void) { return 100; }
+
+int wo_timing_enable(int on) {
+  std::lock_guard<std::mutex> lk(wo::g_tmu);
+  wo::g_timing = on != 0;
+  return WO_OK;
+}
+
+int wo_timing_report(char* buf, size_t len) {
+  std::vector<wo::TimingRec> recs;
+  {
+    std::lock_guard<std::mutex> lk(wo::g_tmu);
+    recs.swap(wo::g_recs);
+  }
+  std::map<std::string, std::pair<long, double>> agg;
+  int status = WO_OK;
+  for (auto& r : recs) {
+    float ms = 0.f;
+    if (hipEventSynchronize(r.b) != hipSuccess || hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess)
+      status = WO_EHIP;
+    auto& a = agg[r.name];
+    a.first += 1;
+    a.second += ms;
+  }
+  {
+    std::lock_guard<std::mutex> lk(wo::g_tmu);
+    for (auto& r : recs) {
+      wo::g_pool.push_back(r.a);
+      wo::g_pool.push_back(r.b);
+    }
+  }
+  std::string out;
+  for (auto& kv : agg) {
+    char line[256];
+    snprintf(line, sizeof(line), "%s %ld %.6f\n", kv.first.c_str(), kv.second.first, kv.second.second);
+    out += line;
+  }
+  if (buf && len) {
+    size_t n = out.size() < len - 1 ? out.size() : len - 1;
+    memcpy(buf, out.data(), n);
+    buf[n] = 0;
+  }
+  return status;
+}
+
+const char* wo_strerror(int status) {
+  switch (status) {
+    case WO_OK: return "ok";
+    case WO_EINVAL: return "invalid argument or optics outside the model's validity";
+    case WO_EUNSUPPORTED: return "unsupported size or mode";
+    case WO_ENOMEM: return "workspace too small";
+    case WO_EHIP: return "HIP runtime error";
+    case WO_EALIAS: return "transfer-function support exceeds the sampled band";
+    default: return "unknown status";
+  }
+}
+
+int wo_bank_shape(const wo_optics* o, int32_t* C, int32_t* P, int32_t* dims, int64_t* elems) {
+  Shape s;
+  if (!o || !bank_shape(o, &s)) return WO_EINVAL;
+  if (C) *C = s.C;
+  if (P) *P = s.P;
+  if (dims) *dims = s.dims;
+  if (elems) *elems = bank_elems(s);
+  return WO_OK;
+}
+
+size_t wo_workspace_size(const wo_optics* o, int32_t n, int32_t op) {
+  Shape s;
+  if (!o || n < 1 || !bank_shape(o, &s)) return 0;
+  if (op == WO_OP_TRANSFER_FUNCTION) return tf_ws(o, n, s);
+  if (op == WO_OP_FORWARD || op == WO_OP_RECONSTRUCT || op == WO_OP_ADJOINT) return linear_ws(n, s);
+  return 0;
+}
+
+int wo_transfer_function(const wo_optics* o, int32_t n, void* tf_out, void* ws, size_t ws_bytes,
+                         void* stream) {
+  int st = validate(o, n);
+  if (st) return st;
+  if (!tf_out || !ws) return WO_EINVAL;
+  Shape s;
+  bank_shape(o, &s);
+  if (ws_bytes < tf_ws(o, n, s)) return WO_ENOMEM;
+  hipStream_t hs = (hipStream_t)stream;
+  std::vector<DevOptics> h(n);
+  for (int i = 0; i < n; ++i) {
+    DevOptics& d = h[i];
+    memset(&d, 0, sizeof(d));
+    d.wavelength = o[i].wavelength;
+    d.na_ill = o[i].na_ill;
+    d.na_det = o[i].na_det;
+    d.n_medium = o[i].n_medium;
+    d.defocus = o[i].defocus;
+    d.tilt_zenith = o[i].tilt_zenith;
+    d.tilt_azimuth = o[i].tilt_azimuth;
+    d.edge_width = o[i].edge_width;
+    if (o[i].model == WO_MODEL_POL5_3D) pol5_kappa(o[i].swing, d.kappa);
+  }
+  char* w = (char*)ws;
+  DevOptics* dopt = (DevOptics*)w;
+  w += params_bytes(n);
+  const int nf = o->model == WO_MODEL_FLUOR_3D ? 1 : 2;
+  float2* ab = (float2*)w;
+  w += align_up((size_t)n * nf * s.Z * s.Y * s.X * sizeof(float2));
+  WO_TRY(launch_set_params(dopt, h.data(), n, hs));
+  const Sampling sm = sampling_of(o);
+  WO_TRY(launch_pupil_sums(dopt, sm, n, hs));
+  WO_TRY(launch_tf_fields_y(dopt, sm, n, ab, hs));
+  float2* tf = (float2*)tf_out;
+  const long M = s.Y * s.Xh;
+  const long plane = s.Y * s.Xh;
+  switch (o->model) {
+    case WO_MODEL_FLUOR_3D:
+      WO_TRY(launch_tf_rows_fluor(dopt, sm, n, ab, tf, hs));
+      WO_TRY(launch_cols(tf, (int)s.Y, s.Xh, s.Z, s.Z, n, -1.f, hs, "k_cols_y_tf"));
+      WO_TRY(launch_cols(tf, (int)s.Z, M, 1, 1, n, -1.f, hs, "k_cols_z_tf"));
+      break;
+    case WO_MODEL_LABELFREE_3D:
+      WO_TRY(launch_tf_rows_labelfree(dopt, sm, n, ab, tf, 2 * s.Z * plane, s.Z * plane, plane, hs));
+      WO_TRY(launch_cols(tf, (int)s.Y, s.Xh, 2 * s.Z, 2 * s.Z, n, -1.f, hs, "k_cols_y_tf"));
+      WO_TRY(launch_cols(tf, (int)s.Z, M, 2, 2, n, -1.f, hs, "k_cols_z_tf"));
+      break;
+    case WO_MODEL_LABELFREE_THIN:
+      WO_TRY(launch_tf_rows_labelfree(dopt, sm, n, ab, tf, 2 * s.Z * plane, plane, 2 * plane, hs));
+      WO_TRY(launch_cols(tf, (int)s.Y, s.Xh, 2 * s.Z, 2 * s.Z, n, -1.f, hs, "k_cols_y_tf"));
+      break;
+    case WO_MODEL_POL5_3D: {
+      float2* uw = (float2*)w;
+      WO_TRY(launch_tf_rows_labelfree(dopt, sm, n, ab, uw, 2 * s.Z * plane, s.Z * plane, plane, hs));
+      WO_TRY(launch_cols(uw, (int)s.Y, s.Xh, 2 * s.Z, 2 * s.Z, n, -1.f, hs, "k_cols_y_tf"));
+      WO_TRY(launch_tf_pol5_z(dopt, sm, n, uw, tf, hs));
+      break;
+    }
+    default:
+      return WO_EINVAL;
+  }
+  return WO_OK;
+}
+
+int wo_forward(const wo_optics* o, int32_t n, const void* tf, const float* f, const float* b,
+               float* d_out, void* ws, size_t ws_bytes, void* stream) {
+  if (!o || n < 1) return WO_EINVAL;
+  int st = check_sampling(o);
+  if (st) return st;
+  for (int i = 1; i < n; ++i)
+    if (!same_sampling(&o[0], &o[i])) return WO_EINVAL;
+  if (!tf || !f || !d_out || !ws) return WO_EINVAL;
+  Shape s;
+  bank_shape(o, &s);
+  if (s.P != 1 && s.P != 2 && s.P != 4) return WO_EUNSUPPORTED;
+  if (ws_bytes < linear_ws(n, s)) return WO_ENOMEM;
+  return run_linear(o, n, s, (const float2*)tf, f, d_out, b, kModeForward, 0.f, ws,
+                    (hipStream_t)stream);
+}
+
+int wo_reconstruct(const wo_optics* o, int32_t n, const void* tf, const float* d, const float* b,
+                   double eta, float* f_out, void* ws, size_t ws_bytes, void* stream) {
+  if (!o || n < 1) return WO_EINVAL;
+  int st = check_sampling(o);
+  if (st) return st;
+  for (int i = 1; i < n; ++i)
+    if (!same_sampling(&o[0], &o[i])) return WO_EINVAL;
+  if (!tf || !d || !f_out || !ws) return WO_EINVAL;
+  if (!(eta >= 0.0) || !isfinite(eta)) return WO_EINVAL;
+  Shape s;
+  bank_shape(o, &s);
+  if (s.P != 1 && s.P != 2 && s.P != 4) return WO_EUNSUPPORTED;
+  if (eta == 0.0 && s.P != 1) return WO_EUNSUPPORTED;
+  if (ws_bytes < linear_ws(n, s)) return WO_ENOMEM;
+  return run_linear(o, n, s, (const float2*)tf, d, f_out, b, kModeSolve, (float)eta, ws,
+                    (hipStream_t)stream);
+}
+
+int wo_adjoint(const wo_optics* o, int32_t n, const void* tf, const float* r, float* g_out,
+               void* ws, size_t ws_bytes, void* stream) {
+  if (!o || n < 1) return WO_EINVAL;
+  int st = check_sampling(o);
+  if (st) return st;
+  for (int i = 1; i < n; ++i)
+    if (!same_sampling(&o[0], &o[i])) return WO_EINVAL;
+  if (!tf || !r || !g_out || !ws) return WO_EINVAL;
+  Shape s;
+  bank_shape(o, &s);
+  if (s.P != 1 && s.P != 2 && s.P != 4) return WO_EUNSUPPORTED;
+  if (ws_bytes < linear_ws(n, s)) return WO_ENOMEM;
+  return run_linear(o, n, s, (const float2*)tf, r, g_out, nullptr, kModeAdjoint, 0.f, ws,
+                    (hipStream_t)stream);
+}
+
+}  // extern "C"

@@ -1,0 +1,288 @@
+// Shared device helpers: complex arithmetic, the LDS Stockham FFT core and
+// the per-patch optics record used by the transfer-function kernels.
+//
+// FFT core: a mixed-radix (2, 3, 4, 5, 8) Stockham autosort transform of
+// `nl` lines held in LDS.  Each pass reads every butterfly's inputs into
+// registers, synchronises, and writes the outputs back in place, so one LDS
+// buffer suffices.  Radices are a runtime plan (one switch per pass); the
+// per-thread register arrays are sized statically from EMAX, the maximum
+// number of elements a thread owns (lines * n <= threads * EMAX).
+// Twiddles W_n^m are generated per workgroup in FP64 and stored in LDS as
+// FP32, so the FFT needs no global table.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace wo {
+
+constexpr int kMaxPasses = 16;
+constexpr int kEmax = 16;          // elements owned by one thread in an LDS FFT
+
+struct FftPlan {
+  int n;
+  int npass;
+  int radix[kMaxPasses];
+};
+
+// Host-side factorisation: as many radix-8 passes as possible, then 4, 2, 3, 5.
+// Returns false when n has a prime factor other than 2, 3, 5.
+inline bool make_plan(int n, FftPlan* p) {
+  p->n = n;
+  p->npass = 0;
+  int m = n;
+  if (n < 1) return false;
+  while (m % 8 == 0 && p->npass < kMaxPasses) { p->radix[p->npass++] = 8; m /= 8; }
+  while (m % 4 == 0 && p->npass < kMaxPasses) { p->radix[p->npass++] = 4; m /= 4; }
+  while (m % 2 == 0 && p->npass < kMaxPasses) { p->radix[p->npass++] = 2; m /= 2; }
+  while (m % 3 == 0 && p->npass < kMaxPasses) { p->radix[p->npass++] = 3; m /= 3; }
+  while (m % 5 == 0 && p->npass < kMaxPasses) { p->radix[p->npass++] = 5; m /= 5; }
+  return m == 1;
+}
+
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ float2 cmulconj(float2 a, float2 b) {  // a * conj(b)
+  return make_float2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
+}
+__device__ __forceinline__ float2 cconj(float2 a) { return make_float2(a.x, -a.y); }
+__device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+__device__ __forceinline__ float2 ctimes_i(float2 a, float s) {  // (s * i) * a, s = +-1
+  return make_float2(-s * a.y, s * a.x);
+}
+
+// ---------------------------------------------------------------- small DFTs
+// sign = -1: forward (exp(-2 pi i nk/R)); +1: inverse (unnormalised).
+
+__device__ __forceinline__ void dft2(float2* v) {
+  float2 a = v[0], b = v[1];
+  v[0] = cadd(a, b);
+  v[1] = csub(a, b);
+}
+
+__device__ __forceinline__ void dft4(float2* v, float s) {
+  float2 a = cadd(v[0], v[2]), b = csub(v[0], v[2]);
+  float2 c = cadd(v[1], v[3]), d = csub(v[1], v[3]);
+  float2 id = ctimes_i(d, s);
+  v[0] = cadd(a, c);
+  v[2] = csub(a, c);
+  v[1] = cadd(b, id);
+  v[3] = csub(b, id);
+}
+
+__device__ __forceinline__ void dft3(float2* v, float s) {
+  const float h = 0.86602540378443864676f;  // sin(2 pi / 3)
+  float2 a = cadd(v[1], v[2]);
+  float2 t = make_float2(v[0].x - 0.5f * a.x, v[0].y - 0.5f * a.y);
+  float2 u = ctimes_i(cscale(csub(v[1], v[2]), h), s);
+  v[0] = cadd(v[0], a);
+  v[1] = cadd(t, u);
+  v[2] = csub(t, u);
+}
+
+__device__ __forceinline__ void dft5(float2* v, float s) {
+  const float c1 = 0.30901699437494742410f;   // cos(2 pi / 5)
+  const float c2 = -0.80901699437494742410f;  // cos(4 pi / 5)
+  const float s1 = 0.95105651629515357212f;   // sin(2 pi / 5)
+  const float s2 = 0.58778525229247312917f;   // sin(4 pi / 5)
+  float2 a1 = cadd(v[1], v[4]), a2 = cadd(v[2], v[3]);
+  float2 b1 = csub(v[1], v[4]), b2 = csub(v[2], v[3]);
+  float2 x0 = v[0];
+  float2 t1 = make_float2(x0.x + c1 * a1.x + c2 * a2.x, x0.y + c1 * a1.y + c2 * a2.y);
+  float2 t2 = make_float2(x0.x + c2 * a1.x + c1 * a2.x, x0.y + c2 * a1.y + c1 * a2.y);
+  float2 u1 = make_float2(s1 * b1.x + s2 * b2.x, s1 * b1.y + s2 * b2.y);
+  float2 u2 = make_float2(s2 * b1.x - s1 * b2.x, s2 * b1.y - s1 * b2.y);
+  float2 iu1 = ctimes_i(u1, s), iu2 = ctimes_i(u2, s);
+  v[0] = make_float2(x0.x + a1.x + a2.x, x0.y + a1.y + a2.y);
+  v[1] = cadd(t1, iu1);
+  v[4] = csub(t1, iu1);
+  v[2] = cadd(t2, iu2);
+  v[3] = csub(t2, iu2);
+}
+
+__device__ __forceinline__ void dft8(float2* v, float s) {
+  const float r = 0.70710678118654752440f;
+  float2 a[4], b[4];
+#pragma unroll
+  for (int n = 0; n < 4; ++n) {
+    a[n] = cadd(v[n], v[n + 4]);
+    b[n] = csub(v[n], v[n + 4]);
+  }
+  // b_n *= W8^n, W8 = exp(s 2 pi i / 8)
+  b[1] = make_float2(r * (b[1].x - s * b[1].y), r * (b[1].y + s * b[1].x));
+  b[2] = ctimes_i(b[2], s);
+  b[3] = make_float2(r * (-b[3].x - s * b[3].y), r * (-b[3].y + s * b[3].x));
+  dft4(a, s);
+  dft4(b, s);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    v[2 * k] = a[k];
+    v[2 * k + 1] = b[k];
+  }
+}
+
+template <int R>
+__device__ __forceinline__ void dft_small(float2* v, float s) {
+  if constexpr (R == 2) dft2(v);
+  else if constexpr (R == 3) dft3(v, s);
+  else if constexpr (R == 4) dft4(v, s);
+  else if constexpr (R == 5) dft5(v, s);
+  else if constexpr (R == 8) dft8(v, s);
+}
+
+// Twiddles tw[m] = exp(-2 pi i m / n), m < n, computed in FP64.
+__device__ __forceinline__ void fill_twiddles(float2* tw, int n, int tid, int nthr) {
+  for (int m = tid; m < n; m += nthr) {
+    double sn, cs;
+    sincospi(-2.0 * (double)m / (double)n, &sn, &cs);
+    tw[m] = make_float2((float)cs, (float)sn);
+  }
+}
+
+// Line layout in LDS: element i of line l lives at lds[line_base(l) + i * es].
+// linefast == true maps consecutive butterfly slots to consecutive lines
+// (use when lines are adjacent in LDS, es = number of lines); otherwise
+// consecutive slots walk along a line (use for row layouts, es = 1).
+struct LdsLines {
+  int nl;     // number of lines
+  int es;     // element stride
+  int ls;     // line stride
+  bool linefast;
+};
+
+template <int R>
+__device__ __forceinline__ void stockham_pass(float2* lds, const LdsLines L, int n, int ns,
+                                              const float2* tw, float s, int tid, int nthr) {
+  constexpr int BPT = (kEmax + R - 1) / R;
+  const int nb = n / R;
+  const int total = L.nl * nb;
+  const int twstep = n / (ns * R);
+  float2 v[BPT][R];
+  int base[BPT], kk[BPT];
+#pragma unroll
+  for (int b = 0; b < BPT; ++b) {
+    const int j = tid + b * nthr;
+    base[b] = -1;
+    if (j < total) {
+      int l, k;
+      if (L.linefast) { l = j % L.nl; k = j / L.nl; }
+      else { k = j % nb; l = j / nb; }
+      const int lb = l * L.ls;
+      const int km = k % ns;
+      base[b] = lb;
+      kk[b] = k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        float2 x = lds[lb + (k + r * nb) * L.es];
+        if (r > 0) {
+          float2 w = tw[r * km * twstep];
+          if (s > 0.f) w.y = -w.y;
+          x = cmul(x, w);
+        }
+        v[b][r] = x;
+      }
+      dft_small<R>(v[b], s);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int b = 0; b < BPT; ++b) {
+    if (base[b] >= 0) {
+      const int k = kk[b];
+      const int d0 = (k / ns) * ns * R + (k % ns);
+#pragma unroll
+      for (int r = 0; r < R; ++r) lds[base[b] + (d0 + r * ns) * L.es] = v[b][r];
+    }
+  }
+  __syncthreads();
+}
+
+// In-place FFT of all lines.  Caller must have synchronised after filling LDS
+// (data and twiddles).  s = -1 forward, +1 inverse (unnormalised).
+__device__ __forceinline__ void lds_fft(float2* lds, const LdsLines L, const FftPlan& p,
+                                        const float2* tw, float s, int tid, int nthr) {
+  int ns = 1;
+  for (int q = 0; q < p.npass; ++q) {
+    const int R = p.radix[q];
+    switch (R) {
+      case 8: stockham_pass<8>(lds, L, p.n, ns, tw, s, tid, nthr); break;
+      case 4: stockham_pass<4>(lds, L, p.n, ns, tw, s, tid, nthr); break;
+      case 2: stockham_pass<2>(lds, L, p.n, ns, tw, s, tid, nthr); break;
+      case 3: stockham_pass<3>(lds, L, p.n, ns, tw, s, tid, nthr); break;
+      case 5: stockham_pass<5>(lds, L, p.n, ns, tw, s, tid, nthr); break;
+      default: break;
+    }
+    ns *= R;
+  }
+}
+
+// ---------------------------------------------------------------- optics
+
+enum Model { kFluor3D = 0, kLabelFree3D = 1, kLabelFreeThin = 2, kPol5 = 3 };
+
+// Per-patch optical parameters on the device (float64).  ``ibg`` is written
+// by the pupil-sum kernel: sum S P^2 (label-free) or sum P^2 (fluorescence).
+struct DevOptics {
+  double wavelength, na_ill, na_det, n_medium;
+  double defocus, tilt_zenith, tilt_azimuth;
+  double edge_width;       // half-width of the soft edge, in frequency pixels
+  double kappa[5][4][2];   // polarisation coupling (re, im), pol5 only
+  double ibg;
+  double pad[3];
+};
+
+// Sampling shared by every patch of a call.
+struct Sampling {
+  int model;
+  int nz, ny, nx;
+  double dz, dy, dx;
+};
+
+__device__ __forceinline__ double fftfreq(int k, int n, double d) {
+  const double val = 1.0 / ((double)n * d);
+  const int ks = (k < (n + 1) / 2) ? k : k - n;
+  return (double)ks * val;
+}
+
+__device__ __forceinline__ double edge_profile(double inside, double hw) {
+  if (hw == 0.0) return inside >= 0.0 ? 1.0 : 0.0;
+  double t = (inside / hw + 1.0) * 0.5;
+  t = t < 0.0 ? 0.0 : (t > 1.0 ? 1.0 : t);
+  return t * t * (3.0 - 2.0 * t);
+}
+
+// d edge / d inside (0 for the hard edge)
+__device__ __forceinline__ double edge_slope(double inside, double hw) {
+  if (hw == 0.0) return 0.0;
+  const double t = (inside / hw + 1.0) * 0.5;
+  if (t <= 0.0 || t >= 1.0) return 0.0;
+  return 6.0 * t * (1.0 - t) * (0.5 / hw);
+}
+
+__device__ __forceinline__ double disc(double fy, double fx, double radius, double hw) {
+  const double r2 = fy * fy + fx * fx;
+  if (hw == 0.0) return r2 <= radius * radius ? 1.0 : 0.0;
+  return edge_profile(radius - sqrt(r2), hw);
+}
+
+__device__ __forceinline__ double soft_halfwidth(const DevOptics& o, const Sampling& sm) {
+  const double dnu = fmin(1.0 / ((double)sm.nx * sm.dx), 1.0 / ((double)sm.ny * sm.dy));
+  return o.edge_width * dnu;
+}
+
+__device__ __forceinline__ void source_centre(const DevOptics& o, double* cy, double* cx) {
+  const double r = o.n_medium * sin(o.tilt_zenith) / o.wavelength;
+  *cy = r * sin(o.tilt_azimuth);
+  *cx = r * cos(o.tilt_azimuth);
+}
+
+// Axial PSF coordinate of plane k: FFT order for 3D models, centred planes for thin.
+__device__ __forceinline__ double plane_z(int k, const Sampling& sm) {
+  if (sm.model == kLabelFreeThin) return sm.dz * ((double)k - 0.5 * (double)(sm.nz - 1));
+  const int ks = (k < (sm.nz + 1) / 2) ? k : k - sm.nz;
+  return sm.dz * (double)ks;
+}
+
+}  // namespace wo

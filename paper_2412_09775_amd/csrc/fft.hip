@@ -1,0 +1,431 @@
+// FFT passes and the per-frequency operators of the linear model.
+//
+// A 3D real transform is three passes over HBM: rows along X (real <-> half
+// spectrum, two real rows packed into one complex line), columns along Y
+// (strided, tiles of W contiguous half-spectrum columns staged through LDS),
+// and columns along Z.  The Z pass is fused with the per-frequency operator
+// (forward H F, Tikhonov solve, or adjoint H^H R) and the inverse Z transform,
+// so the spectrum of every channel visits HBM once between the Y passes.
+#include "internal.hpp"
+
+namespace wo {
+
+static int threads_for(long elems) {
+  long t = (elems + kEmax - 1) / kEmax;
+  t = ((t + 63) / 64) * 64;
+  if (t < 64) t = 64;
+  if (t > 1024) t = 1024;
+  return (int)t;
+}
+
+// ------------------------------------------------------------------ rows
+
+__device__ __forceinline__ long group_row(long r, long rpg, long stride) {
+  const long g = r / rpg;
+  return g * stride + (r - g * rpg);
+}
+
+__global__ __launch_bounds__(1024) void k_rows_r2c(const float* __restrict__ in,
+                                                   float2* __restrict__ out, int X, RowGroups g,
+                                                   FftPlan plan, int lines_per_wg, long nlines) {
+  extern __shared__ float2 smem[];
+  float2* tw = smem;
+  float2* buf = smem + X;
+  __shared__ long rin[2 * 64], rout[2 * 64];
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  fill_twiddles(tw, X, tid, nthr);
+  const long nrows = g.rows_per_group * g.ngroups;
+  const long line0 = (long)blockIdx.x * lines_per_wg;
+  const int nl = (int)min((long)lines_per_wg, nlines - line0);
+  for (int t = tid; t < 2 * nl; t += nthr) {
+    const long r = 2 * line0 + t;
+    rin[t] = r < nrows ? group_row(r, g.rows_per_group, g.in_stride) : -1;
+    rout[t] = r < nrows ? group_row(r, g.rows_per_group, g.out_stride) : -1;
+  }
+  __syncthreads();
+  for (int e = tid; e < nl * X; e += nthr) {
+    const int l = e / X, i = e - l * X;
+    const float a = in[rin[2 * l] * X + i];
+    const float b = rin[2 * l + 1] >= 0 ? in[rin[2 * l + 1] * X + i] : 0.f;
+    buf[e] = make_float2(a, b);
+  }
+  __syncthreads();
+  lds_fft(buf, LdsLines{nl, 1, X, false}, plan, tw, -1.f, tid, nthr);
+  const int Xh = X / 2 + 1;
+  for (int e = tid; e < nl * Xh; e += nthr) {
+    const int l = e / Xh, k = e - l * Xh;
+    const float2 zk = buf[l * X + k];
+    const float2 zm = buf[l * X + (k == 0 ? 0 : X - k)];
+    const float2 A = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y));
+    const float2 B = make_float2(0.5f * (zk.y + zm.y), -0.5f * (zk.x - zm.x));
+    out[rout[2 * l] * Xh + k] = A;
+    if (rout[2 * l + 1] >= 0) out[rout[2 * l + 1] * Xh + k] = B;
+  }
+}
+
+__global__ __launch_bounds__(1024) void k_rows_c2r(const float2* __restrict__ in,
+                                                   float* __restrict__ out, int X, RowGroups g,
+                                                   FftPlan plan, int lines_per_wg, long nlines,
+                                                   float scale) {
+  extern __shared__ float2 smem[];
+  float2* tw = smem;
+  float2* buf = smem + X;
+  __shared__ long rin[2 * 64], rout[2 * 64];
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  fill_twiddles(tw, X, tid, nthr);
+  const long nrows = g.rows_per_group * g.ngroups;
+  const long line0 = (long)blockIdx.x * lines_per_wg;
+  const int nl = (int)min((long)lines_per_wg, nlines - line0);
+  for (int t = tid; t < 2 * nl; t += nthr) {
+    const long r = 2 * line0 + t;
+    rin[t] = r < nrows ? group_row(r, g.rows_per_group, g.in_stride) : -1;
+    rout[t] = r < nrows ? group_row(r, g.rows_per_group, g.out_stride) : -1;
+  }
+  __syncthreads();
+  const int Xh = X / 2 + 1;
+  for (int e = tid; e < nl * X; e += nthr) {
+    const int l = e / X, k = e - l * X;
+    const bool mirror = 2 * k > X;
+    const int kk = mirror ? X - k : k;
+    float2 A = in[rin[2 * l] * Xh + kk];
+    float2 B = rin[2 * l + 1] >= 0 ? in[rin[2 * l + 1] * Xh + kk] : make_float2(0.f, 0.f);
+    if (kk == 0 || 2 * kk == X) { A.y = 0.f; B.y = 0.f; }   // Re of the inverse ignores them
+    if (mirror) { A.y = -A.y; B.y = -B.y; }
+    buf[e] = make_float2(A.x - B.y, A.y + B.x);
+  }
+  __syncthreads();
+  lds_fft(buf, LdsLines{nl, 1, X, false}, plan, tw, 1.f, tid, nthr);
+  for (int e = tid; e < nl * X; e += nthr) {
+    const int l = e / X, i = e - l * X;
+    const float2 v = buf[e];
+    out[rout[2 * l] * X + i] = v.x * scale;
+    if (rout[2 * l + 1] >= 0) out[rout[2 * l + 1] * X + i] = v.y * scale;
+  }
+}
+
+static int lines_per_wg_for(int X) {
+  int L = 4096 / X;
+  if (L < 1) L = 1;
+  if (L > 64) L = 64;
+  while (L > 1 && (long)L * X > 16384) --L;
+  return L;
+}
+
+hipError_t launch_rows_r2c(const float* in, float2* out, int X, const RowGroups& g, hipStream_t s) {
+  FftPlan plan;
+  if (!make_plan(X, &plan)) return hipErrorInvalidValue;
+  const long nrows = g.rows_per_group * g.ngroups;
+  const long nlines = (nrows + 1) / 2;
+  const int L = lines_per_wg_for(X);
+  const long nwg = (nlines + L - 1) / L;
+  const int thr = threads_for((long)L * X);
+  const size_t lds = (size_t)(X + L * X) * sizeof(float2);
+  { ScopedTiming _t("k_rows_r2c", s);
+  hipLaunchKernelGGL(k_rows_r2c, dim3((unsigned)nwg), dim3(thr), lds, s, in, out, X, g, plan, L,
+                     nlines); }
+  return hipGetLastError();
+}
+
+hipError_t launch_rows_c2r(const float2* in, float* out, int X, const RowGroups& g, float scale,
+                           hipStream_t s) {
+  FftPlan plan;
+  if (!make_plan(X, &plan)) return hipErrorInvalidValue;
+  const long nrows = g.rows_per_group * g.ngroups;
+  const long nlines = (nrows + 1) / 2;
+  const int L = lines_per_wg_for(X);
+  const long nwg = (nlines + L - 1) / L;
+  const int thr = threads_for((long)L * X);
+  const size_t lds = (size_t)(X + L * X) * sizeof(float2);
+  { ScopedTiming _t("k_rows_c2r", s);
+  hipLaunchKernelGGL(k_rows_c2r, dim3((unsigned)nwg), dim3(thr), lds, s, in, out, X, g, plan, L,
+                     nlines, scale); }
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ columns
+
+__global__ __launch_bounds__(1024) void k_cols(float2* __restrict__ data, int N, long M, int W,
+                                               long tiles_m, long planes_per_group,
+                                               long group_stride, FftPlan plan, float sign) {
+  extern __shared__ float2 smem[];
+  float2* tw = smem;
+  float2* buf = smem + N;
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  fill_twiddles(tw, N, tid, nthr);
+  const long bid = blockIdx.x;
+  const long tile = bid % tiles_m;
+  const long plane = bid / tiles_m;
+  const long pg = plane / planes_per_group, pi = plane - pg * planes_per_group;
+  float2* base = data + (pg * group_stride + pi) * (long)N * M;
+  const long m0 = tile * W;
+  const int weff = (int)min((long)W, M - m0);
+  for (int e = tid; e < N * W; e += nthr) {
+    const int n = e / W, w = e - n * W;
+    buf[e] = w < weff ? base[(long)n * M + m0 + w] : make_float2(0.f, 0.f);
+  }
+  __syncthreads();
+  lds_fft(buf, LdsLines{W, W, 1, true}, plan, tw, sign, tid, nthr);
+  for (int e = tid; e < N * W; e += nthr) {
+    const int n = e / W, w = e - n * W;
+    if (w < weff) base[(long)n * M + m0 + w] = buf[e];
+  }
+}
+
+// Column tile width: W contiguous complex values per row (W = 16 is one
+// 128-byte segment), limited by the elements a workgroup may own and by the
+// device's LDS per workgroup (twiddles + tile).
+static int tile_width(int n, int ch) {
+  const long lim = lds_limit_bytes() / (long)sizeof(float2);
+  int W = 16;
+  while (W > 1 && ((long)W * n * ch > 16384 || n + (long)W * n * ch > lim)) W /= 2;
+  return W;
+}
+
+hipError_t launch_cols(float2* data, int N, long M, long planes_per_group, long group_stride,
+                       long ngroups, float sign, hipStream_t s, const char* tag) {
+  FftPlan plan;
+  if (!make_plan(N, &plan)) return hipErrorInvalidValue;
+  const int W = tile_width(N, 1);
+  const long tiles = (M + W - 1) / W;
+  const long nwg = tiles * planes_per_group * ngroups;
+  const int thr = threads_for((long)N * W);
+  const size_t lds = (size_t)(N + N * W) * sizeof(float2);
+  { ScopedTiming _t(tag, s);
+  hipLaunchKernelGGL(k_cols, dim3((unsigned)nwg), dim3(thr), lds, s, data, N, M, W, tiles,
+                     planes_per_group, group_stride, plan, sign); }
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ per-frequency operators
+//
+// Channel values of one frequency sit at cell[ch * cs].  tfp points at the
+// (c = 0, p = 0) TF value of this frequency; entry (c, p) is at tfp[(c*P+p)*ts].
+// forward: y_c = sum_p H_cp x_p (+ N b_c at DC)
+// solve:   F = (H^H H + eta I)^-1 H^H (x - N b delta)      (Eq. tls_solution)
+// adjoint: y_p = sum_c conj(H_cp) x_c
+// Outputs are scaled by inv_n (the 1/N of the inverse transform).
+
+template <int P>
+__device__ __forceinline__ void freq_op(float2* cell, long cs, const float2* __restrict__ tfp,
+                                        long ts, int C, int mode, float eta,
+                                        const float* __restrict__ bg, bool dc, float n_full,
+                                        float inv_n) {
+  if (mode == kModeForward) {
+    float2 x[P];
+#pragma unroll
+    for (int p = 0; p < P; ++p) x[p] = cell[p * cs];
+    for (int c = 0; c < C; ++c) {
+      float2 y = make_float2(0.f, 0.f);
+#pragma unroll
+      for (int p = 0; p < P; ++p) y = cadd(y, cmul(tfp[(long)(c * P + p) * ts], x[p]));
+      if (dc && bg) y.x += n_full * bg[c];
+      cell[c * cs] = cscale(y, inv_n);
+    }
+    return;
+  }
+  if (mode == kModeAdjoint) {
+    float2 y[P];
+#pragma unroll
+    for (int p = 0; p < P; ++p) y[p] = make_float2(0.f, 0.f);
+    for (int c = 0; c < C; ++c) {
+      const float2 xc = cell[c * cs];
+#pragma unroll
+      for (int p = 0; p < P; ++p) y[p] = cadd(y[p], cmul(cconj(tfp[(long)(c * P + p) * ts]), xc));
+    }
+#pragma unroll
+    for (int p = 0; p < P; ++p) cell[p * cs] = cscale(y[p], inv_n);
+    return;
+  }
+  // solve: accumulate the P x P normal matrix (lower triangle) and H^H x
+  float2 m[P][P];
+  float2 r[P];
+#pragma unroll
+  for (int p = 0; p < P; ++p) {
+    r[p] = make_float2(0.f, 0.f);
+#pragma unroll
+    for (int q = 0; q < P; ++q) m[p][q] = make_float2(0.f, 0.f);
+  }
+  for (int c = 0; c < C; ++c) {
+    float2 xc = cell[c * cs];
+    if (dc && bg) xc.x -= n_full * bg[c];
+    float2 h[P];
+#pragma unroll
+    for (int p = 0; p < P; ++p) h[p] = tfp[(long)(c * P + p) * ts];
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+      r[p] = cadd(r[p], cmul(cconj(h[p]), xc));
+#pragma unroll
+      for (int q = 0; q <= p; ++q) m[p][q] = cadd(m[p][q], cmul(cconj(h[p]), h[q]));
+    }
+  }
+  // m[p][q] (p >= q) holds the lower triangle of M = H^H H, M_pq = sum_c conj(H_cp) H_cq.
+  float2 F[P];
+  if (P == 1) {
+    const float den = m[0][0].x + eta;
+    F[0] = den > 0.f ? cscale(r[0], 1.f / den) : make_float2(0.f, 0.f);
+  } else {
+    // Cholesky M = L L^H with M_pq (p >= q) = m[p][q]
+    float2 L[P][P];
+    float dinv[P];
+#pragma unroll
+    for (int j = 0; j < P; ++j) {
+      float d = m[j][j].x + eta;
+#pragma unroll
+      for (int k = 0; k < j; ++k) d -= L[j][k].x * L[j][k].x + L[j][k].y * L[j][k].y;
+      const float lj = sqrtf(fmaxf(d, 1e-37f));
+      dinv[j] = 1.f / lj;
+#pragma unroll
+      for (int i = j + 1; i < P; ++i) {
+        float2 v = m[i][j];
+#pragma unroll
+        for (int k = 0; k < j; ++k) v = csub(v, cmulconj(L[i][k], L[j][k]));
+        L[i][j] = cscale(v, dinv[j]);
+      }
+    }
+    float2 y[P];
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+      float2 v = r[i];
+#pragma unroll
+      for (int k = 0; k < i; ++k) v = csub(v, cmul(L[i][k], y[k]));
+      y[i] = cscale(v, dinv[i]);
+    }
+#pragma unroll
+    for (int i = P - 1; i >= 0; --i) {
+      float2 v = y[i];
+#pragma unroll
+      for (int k = i + 1; k < P; ++k) v = csub(v, cmul(cconj(L[k][i]), F[k]));
+      F[i] = cscale(v, dinv[i]);
+    }
+  }
+#pragma unroll
+  for (int p = 0; p < P; ++p) cell[p * cs] = cscale(F[p], inv_n);
+}
+
+template <int P>
+__global__ __launch_bounds__(1024) void k_zop(float2* __restrict__ spec,
+                                              const float2* __restrict__ tf, int C, int Z, long M,
+                                              int slots, int W, long tiles_m, FftPlan plan,
+                                              int mode, float eta, const float* __restrict__ bg,
+                                              float inv_n, float n_full) {
+  extern __shared__ float2 smem[];
+  float2* tw = smem;
+  float2* buf = smem + Z;
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  fill_twiddles(tw, Z, tid, nthr);
+  const long bid = blockIdx.x;
+  const long tile = bid % tiles_m;
+  const long patch = bid / tiles_m;
+  const int cin = mode == kModeForward ? P : C;
+  const int cout = mode == kModeForward ? C : P;
+  const int CH = cin > cout ? cin : cout;
+  float2* sp = spec + patch * (long)slots * Z * M;
+  const float2* tp = tf + patch * (long)C * P * Z * M;
+  const float* bp = bg ? bg + patch * C : nullptr;
+  const long m0 = tile * W;
+  const int weff = (int)min((long)W, M - m0);
+  for (int e = tid; e < cin * Z * W; e += nthr) {
+    const int w = e % W;
+    const int t = e / W;
+    const int z = t % Z, ch = t / Z;
+    buf[(z * CH + ch) * W + w] = w < weff ? sp[((long)ch * Z + z) * M + m0 + w] : make_float2(0.f, 0.f);
+  }
+  __syncthreads();
+  lds_fft(buf, LdsLines{cin * W, CH * W, 1, true}, plan, tw, -1.f, tid, nthr);
+  for (int f = tid; f < Z * W; f += nthr) {
+    const int z = f / W, w = f - z * W;
+    if (w >= weff) continue;
+    const long m = m0 + w;
+    freq_op<P>(buf + (long)z * CH * W + w, W, tp + (long)z * M + m, (long)Z * M, C, mode, eta, bp,
+               z == 0 && m == 0, n_full, inv_n);
+  }
+  __syncthreads();
+  lds_fft(buf, LdsLines{cout * W, CH * W, 1, true}, plan, tw, 1.f, tid, nthr);
+  for (int e = tid; e < cout * Z * W; e += nthr) {
+    const int w = e % W;
+    const int t = e / W;
+    const int z = t % Z, ch = t / Z;
+    if (w < weff) sp[((long)ch * Z + z) * M + m0 + w] = buf[(z * CH + ch) * W + w];
+  }
+}
+
+hipError_t launch_zop(float2* spec, const float2* tf, int C, int P, int Z, long M, int slots,
+                      int npatch, int mode, float eta, const float* bg, float inv_n, double n_full,
+                      hipStream_t s) {
+  FftPlan plan;
+  if (!make_plan(Z, &plan)) return hipErrorInvalidValue;
+  const int cin = mode == kModeForward ? P : C;
+  const int cout = mode == kModeForward ? C : P;
+  const int CH = cin > cout ? cin : cout;
+  const int W = tile_width(Z, CH);
+  const long tiles = (M + W - 1) / W;
+  const long nwg = tiles * npatch;
+  const int thr = threads_for((long)CH * Z * W);
+  const size_t lds = (size_t)(Z + CH * Z * W) * sizeof(float2);
+  const float nf = (float)n_full;
+  switch (P) {
+    case 1:
+      { ScopedTiming _t("k_zop<1>", s);
+      hipLaunchKernelGGL(k_zop<1>, dim3((unsigned)nwg), dim3(thr), lds, s, spec, tf, C, Z, M, slots,
+                         W, tiles, plan, mode, eta, bg, inv_n, nf); }
+      break;
+    case 2:
+      { ScopedTiming _t("k_zop<2>", s);
+      hipLaunchKernelGGL(k_zop<2>, dim3((unsigned)nwg), dim3(thr), lds, s, spec, tf, C, Z, M, slots,
+                         W, tiles, plan, mode, eta, bg, inv_n, nf); }
+      break;
+    case 4:
+      { ScopedTiming _t("k_zop<4>", s);
+      hipLaunchKernelGGL(k_zop<4>, dim3((unsigned)nwg), dim3(thr), lds, s, spec, tf, C, Z, M, slots,
+                         W, tiles, plan, mode, eta, bg, inv_n, nf); }
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <int P>
+__global__ __launch_bounds__(256) void k_op2d(float2* __restrict__ spec,
+                                              const float2* __restrict__ tf, int C, long M,
+                                              int slots, int mode, float eta,
+                                              const float* __restrict__ bg, float inv_n,
+                                              float n_full, long blocks_per_patch) {
+  const long patch = blockIdx.x / blocks_per_patch;
+  const long m = (blockIdx.x - patch * blocks_per_patch) * (long)blockDim.x + threadIdx.x;
+  if (m >= M) return;
+  float2* sp = spec + patch * (long)slots * M;
+  const float2* tp = tf + patch * (long)C * P * M;
+  const float* bp = bg ? bg + patch * C : nullptr;
+  freq_op<P>(sp + m, M, tp + m, M, C, mode, eta, bp, m == 0, n_full, inv_n);
+}
+
+hipError_t launch_op2d(float2* spec, const float2* tf, int C, int P, long M, int slots, int npatch,
+                       int mode, float eta, const float* bg, float inv_n, double n_full,
+                       hipStream_t s) {
+  const long bpp = (M + 255) / 256;
+  const long nwg = bpp * npatch;
+  const float nf = (float)n_full;
+  switch (P) {
+    case 1:
+      { ScopedTiming _t("k_op2d<1>", s);
+      hipLaunchKernelGGL(k_op2d<1>, dim3((unsigned)nwg), dim3(256), 0, s, spec, tf, C, M, slots,
+                         mode, eta, bg, inv_n, nf, bpp); }
+      break;
+    case 2:
+      { ScopedTiming _t("k_op2d<2>", s);
+      hipLaunchKernelGGL(k_op2d<2>, dim3((unsigned)nwg), dim3(256), 0, s, spec, tf, C, M, slots,
+                         mode, eta, bg, inv_n, nf, bpp); }
+      break;
+    case 4:
+      { ScopedTiming _t("k_op2d<4>", s);
+      hipLaunchKernelGGL(k_op2d<4>, dim3((unsigned)nwg), dim3(256), 0, s, spec, tf, C, M, slots,
+                         mode, eta, bg, inv_n, nf, bpp); }
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace wo

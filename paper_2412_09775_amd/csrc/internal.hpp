@@ -1,0 +1,74 @@
+// Host-side launchers shared between the translation units of the library.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "common.hpp"
+
+namespace wo {
+
+// Dynamic LDS bytes one workgroup may use on the current device (queried once).
+long lds_limit_bytes();
+
+// Optional per-kernel timing: when enabled, launches are bracketed by HIP
+// events on their own stream; wo_timing_report() sums the elapsed times.
+bool timing_enabled();
+void timing_begin(const char* name, hipStream_t s, void** token);
+void timing_end(void* token, hipStream_t s);
+
+struct ScopedTiming {
+  void* token = nullptr;
+  hipStream_t s;
+  ScopedTiming(const char* name, hipStream_t st) : s(st) {
+    if (timing_enabled()) timing_begin(name, st, &token);
+  }
+  ~ScopedTiming() {
+    if (token) timing_end(token, s);
+  }
+};
+
+// Grouped row addressing: row i of group g lives at row g * stride + i.
+struct RowGroups {
+  long rows_per_group;
+  long in_stride;   // rows between consecutive groups of the input
+  long out_stride;  // rows between consecutive groups of the output
+  long ngroups;
+};
+
+// Real rows -> half-spectrum rows (forward, unnormalised).
+hipError_t launch_rows_r2c(const float* in, float2* out, int X, const RowGroups& g, hipStream_t s);
+// Half-spectrum rows -> real rows times `scale` (inverse).
+hipError_t launch_rows_c2r(const float2* in, float* out, int X, const RowGroups& g, float scale,
+                           hipStream_t s);
+// In-place FFT along the middle axis of planes [N][M]; plane p of group g
+// starts at data + (g * group_stride + p) * N * M.
+hipError_t launch_cols(float2* data, int N, long M, long planes_per_group, long group_stride,
+                       long ngroups, float sign, hipStream_t s, const char* tag = "k_cols");
+
+enum SpectralMode { kModeForward = 0, kModeSolve = 1, kModeAdjoint = 2 };
+
+// 3D: forward Z-FFT, per-frequency op, inverse Z-FFT, fused.  spec holds
+// `slots` channel slots of [Z][M] per patch; tf holds [C][P][Z][M] per patch.
+hipError_t launch_zop(float2* spec, const float2* tf, int C, int P, int Z, long M, int slots,
+                      int npatch, int mode, float eta, const float* bg, float inv_n, double n_full,
+                      hipStream_t s);
+// 2D (thin) per-frequency op: spec [slots][M] per patch, tf [C][P][M] per patch.
+hipError_t launch_op2d(float2* spec, const float2* tf, int C, int P, long M, int slots, int npatch,
+                       int mode, float eta, const float* bg, float inv_n, double n_full,
+                       hipStream_t s);
+
+// Transfer-function synthesis.
+hipError_t launch_set_params(DevOptics* dst, const DevOptics* host, int n, hipStream_t s);
+hipError_t launch_pupil_sums(DevOptics* opt, const Sampling& sm, int npatch, hipStream_t s);
+hipError_t launch_tf_fields_y(const DevOptics* opt, const Sampling& sm, int npatch, float2* ab,
+                              hipStream_t s);
+hipError_t launch_tf_rows_labelfree(const DevOptics* opt, const Sampling& sm, int npatch,
+                                    const float2* ab, float2* out, long patch_stride,
+                                    long pstride, long zstride, hipStream_t s);
+hipError_t launch_tf_rows_fluor(const DevOptics* opt, const Sampling& sm, int npatch,
+                                const float2* h, float2* out, hipStream_t s);
+hipError_t launch_tf_pol5_z(const DevOptics* opt, const Sampling& sm, int npatch, float2* uw,
+                            float2* tf, hipStream_t s);
+
+}  // namespace wo

@@ -1,0 +1,365 @@
+// Transfer-function synthesis (Table 1, scalar column) on the device.
+//
+// Label-free: per plane z, the direct field A_z = S P e^{i 2 pi kz (z - dz0)}
+// and the scattered field B_z = P (i k_m / kz) e^{i 2 pi kz (z - dz0)} are
+// generated on the lateral frequency grid (FP64 arithmetic, FP32 storage) and
+// inverse-transformed along Y; a row kernel finishes the inverse transform
+// along X, forms the point response c = b conj(a) / (X Y I_bg), transforms it
+// forward along X and splits it into the half spectra of 2 Re c (phase) and
+// -2 Im c (absorption).  The remaining Y (and, for 3D models, Z) transforms
+// reuse the generic column passes.  Fluorescence does the same with the single
+// field P e^{i 2 pi kz (z - dz0)} and the real PSF |h|^2 normalised to unit sum.
+#include "internal.hpp"
+
+namespace wo {
+
+static int threads_for_tf(long elems) {
+  long t = (elems + kEmax - 1) / kEmax;
+  t = ((t + 63) / 64) * 64;
+  if (t < 64) t = 64;
+  if (t > 1024) t = 1024;
+  return (int)t;
+}
+
+// ------------------------------------------------------------------ parameters
+
+// Per-patch optics travel as kernel arguments (a batch of up to 8 records per
+// launch), so setting them needs no host staging buffer and stays
+// asynchronous on the stream.
+struct OpticsBatch {
+  DevOptics o[8];
+};
+static_assert(sizeof(OpticsBatch) <= 3584, "kernel arguments are limited to 4 KiB");
+
+__global__ void k_set_params(DevOptics* dst, OpticsBatch b, int count) {
+  const int i = threadIdx.x;
+  if (i < count) dst[i] = b.o[i];
+}
+
+hipError_t launch_set_params(DevOptics* dst, const DevOptics* host, int n, hipStream_t s) {
+  for (int i0 = 0; i0 < n; i0 += 8) {
+    OpticsBatch b;
+    const int cnt = n - i0 < 8 ? n - i0 : 8;
+    for (int j = 0; j < cnt; ++j) b.o[j] = host[i0 + j];
+    hipLaunchKernelGGL(k_set_params, dim3(1), dim3(64), 0, s, dst + i0, b, cnt);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+// ------------------------------------------------------------------ pupil sums
+
+__global__ __launch_bounds__(256) void k_pupil_sums(DevOptics* opt, Sampling sm) {
+  __shared__ double red[256];
+  const int tid = threadIdx.x;
+  const DevOptics o = opt[blockIdx.x];
+  const double hw = soft_halfwidth(o, sm);
+  const double rd = o.na_det / o.wavelength, ri = o.na_ill / o.wavelength;
+  double cy, cx;
+  source_centre(o, &cy, &cx);
+  double acc = 0.0;
+  const long n = (long)sm.ny * sm.nx;
+  for (long idx = tid; idx < n; idx += blockDim.x) {
+    const int ky = (int)(idx / sm.nx), kx = (int)(idx - (long)ky * sm.nx);
+    const double fy = fftfreq(ky, sm.ny, sm.dy), fx = fftfreq(kx, sm.nx, sm.dx);
+    const double P = disc(fy, fx, rd, hw);
+    if (sm.model == kFluor3D) acc += P * P;
+    else acc += disc(fy - cy, fx - cx, ri, hw) * P * P;
+  }
+  red[tid] = acc;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (tid < st) red[tid] += red[tid + st];
+    __syncthreads();
+  }
+  if (tid == 0) opt[blockIdx.x].ibg = red[0];
+}
+
+hipError_t launch_pupil_sums(DevOptics* opt, const Sampling& sm, int npatch, hipStream_t s) {
+  { ScopedTiming _t("k_pupil_sums", s);
+  hipLaunchKernelGGL(k_pupil_sums, dim3(npatch), dim3(256), 0, s, opt, sm); }
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ fields, inverse Y
+
+// ab layout: [patch][field][z][y][x] complex (field 0 = A or the fluorescence
+// field, field 1 = B).
+__global__ __launch_bounds__(1024) void k_tf_fields_y(const DevOptics* __restrict__ opt,
+                                                      Sampling sm, float2* __restrict__ ab, int W,
+                                                      long tiles_x, FftPlan plan) {
+  extern __shared__ float2 smem[];
+  const int Y = sm.ny, X = sm.nx, Z = sm.nz;
+  float2* tw = smem;
+  float2* buf = smem + Y;
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  fill_twiddles(tw, Y, tid, nthr);
+  const long bid = blockIdx.x;
+  const long tile = bid % tiles_x;
+  const long pz = bid / tiles_x;
+  const int z = (int)(pz % Z);
+  const long patch = pz / Z;
+  const DevOptics o = opt[patch];
+  const bool fluor = sm.model == kFluor3D;
+  const int nf = fluor ? 1 : 2;
+  const double hw = soft_halfwidth(o, sm);
+  const double km = o.n_medium / o.wavelength;
+  const double rd = o.na_det / o.wavelength, ri = o.na_ill / o.wavelength;
+  double cy, cx;
+  source_centre(o, &cy, &cx);
+  const double dzr = plane_z(z, sm) - o.defocus;
+  const int x0 = (int)(tile * W);
+  for (int e = tid; e < Y * W; e += nthr) {
+    const int ky = e / W, w = e - ky * W;
+    const int kx = x0 + w;
+    float2 A = make_float2(0.f, 0.f), B = make_float2(0.f, 0.f);
+    if (kx < X) {
+      const double fy = fftfreq(ky, Y, sm.dy), fx = fftfreq(kx, X, sm.dx);
+      const double P = disc(fy, fx, rd, hw);
+      if (P != 0.0) {
+        const double kz = sqrt(fmax(km * km - (fy * fy + fx * fx), 0.0));
+        double sn, cs;
+        sincospi(2.0 * kz * dzr, &sn, &cs);
+        if (fluor) {
+          A = make_float2((float)(P * cs), (float)(P * sn));
+        } else {
+          const double S = disc(fy - cy, fx - cx, ri, hw);
+          A = make_float2((float)(S * P * cs), (float)(S * P * sn));
+          if (kz > 0.0) {
+            const double g = P * km / kz;          // P * (i k_m / kz) * e^{i phi}
+            B = make_float2((float)(-g * sn), (float)(g * cs));
+          }
+        }
+      }
+    }
+    buf[ky * nf * W + w] = A;
+    if (!fluor) buf[ky * nf * W + W + w] = B;
+  }
+  __syncthreads();
+  lds_fft(buf, LdsLines{nf * W, nf * W, 1, true}, plan, tw, 1.f, tid, nthr);
+  for (int e = tid; e < Y * nf * W; e += nthr) {
+    const int ky = e / (nf * W);
+    const int r = e - ky * nf * W;
+    const int f = r / W, w = r - f * W;
+    const int kx = x0 + w;
+    if (kx < X) ab[(((patch * nf + f) * Z + z) * (long)Y + ky) * X + kx] = buf[e];
+  }
+}
+
+hipError_t launch_tf_fields_y(const DevOptics* opt, const Sampling& sm, int npatch, float2* ab,
+                              hipStream_t s) {
+  FftPlan plan;
+  if (!make_plan(sm.ny, &plan)) return hipErrorInvalidValue;
+  const int nf = sm.model == kFluor3D ? 1 : 2;
+  const long lim = lds_limit_bytes() / (long)sizeof(float2);
+  int W = 16;
+  while (W > 1 && ((long)W * nf * sm.ny > 16384 || sm.ny + (long)W * nf * sm.ny > lim)) W /= 2;
+  const long tiles = (sm.nx + W - 1) / W;
+  const long nwg = tiles * sm.nz * (long)npatch;
+  const int thr = threads_for_tf((long)sm.ny * nf * W);
+  const size_t lds = (size_t)(sm.ny + sm.ny * nf * W) * sizeof(float2);
+  { ScopedTiming _t("k_tf_fields_y", s);
+  hipLaunchKernelGGL(k_tf_fields_y, dim3((unsigned)nwg), dim3(thr), lds, s, opt, sm, ab, W, tiles,
+                     plan); }
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ rows: label-free
+
+// out[patch * patch_stride + p * pstride + z * zstride + y * Xh + k], p = 0 phase, 1 absorption
+__global__ __launch_bounds__(1024) void k_tf_rows_lf(const DevOptics* __restrict__ opt,
+                                                     Sampling sm, const float2* __restrict__ ab,
+                                                     float2* __restrict__ out, long patch_stride,
+                                                     long pstride, long zstride, int rows_per_wg,
+                                                     long wg_per_patch, FftPlan plan) {
+  extern __shared__ float2 smem[];
+  const int Y = sm.ny, X = sm.nx, Z = sm.nz, Xh = X / 2 + 1;
+  float2* tw = smem;
+  float2* buf = smem + X;
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  fill_twiddles(tw, X, tid, nthr);
+  const long patch = blockIdx.x / wg_per_patch;
+  const long rpp = (long)Z * Y;
+  const long row0 = (blockIdx.x - patch * wg_per_patch) * (long)rows_per_wg;
+  const int nr = (int)min((long)rows_per_wg, rpp - row0);
+  const float2* a_src = ab + (patch * 2 + 0) * rpp * X;
+  const float2* b_src = ab + (patch * 2 + 1) * rpp * X;
+  for (int e = tid; e < nr * 2 * X; e += nthr) {
+    const int i = e % X;
+    const int t = e / X;
+    const int f = t & 1, r = t >> 1;
+    const float2* src = f ? b_src : a_src;
+    buf[(2 * r + f) * X + i] = src[(row0 + r) * X + i];
+  }
+  __syncthreads();
+  lds_fft(buf, LdsLines{2 * nr, 1, X, false}, plan, tw, 1.f, tid, nthr);
+  const float cs = (float)(1.0 / ((double)X * (double)Y * opt[patch].ibg));
+  for (int e = tid; e < nr * X; e += nthr) {
+    const int r = e / X, i = e - r * X;
+    const float2 a = buf[2 * r * X + i], b = buf[(2 * r + 1) * X + i];
+    buf[2 * r * X + i] = cscale(cmulconj(b, a), cs);
+  }
+  __syncthreads();
+  lds_fft(buf, LdsLines{nr, 1, 2 * X, false}, plan, tw, -1.f, tid, nthr);
+  float2* op = out + patch * patch_stride;
+  for (int e = tid; e < nr * Xh; e += nthr) {
+    const int r = e / Xh, k = e - r * Xh;
+    const float2 Ck = buf[2 * r * X + k];
+    const float2 Cm = buf[2 * r * X + (k == 0 ? 0 : X - k)];
+    const long row = row0 + r;
+    const long z = row / Y, y = row - z * Y;
+    const float2 U = make_float2(Ck.x + Cm.x, Ck.y - Cm.y);          // C + conj(C(-k))
+    const float2 V = make_float2(-(Ck.y + Cm.y), Ck.x - Cm.x);       // i (C - conj(C(-k)))
+    op[z * zstride + y * Xh + k] = U;
+    op[pstride + z * zstride + y * Xh + k] = V;
+  }
+}
+
+hipError_t launch_tf_rows_labelfree(const DevOptics* opt, const Sampling& sm, int npatch,
+                                    const float2* ab, float2* out, long patch_stride,
+                                    long pstride, long zstride, hipStream_t s) {
+  FftPlan plan;
+  if (!make_plan(sm.nx, &plan)) return hipErrorInvalidValue;
+  int R = 2048 / sm.nx;                       // rows per workgroup (2 lines each)
+  if (R < 1) R = 1;
+  while (R > 1 && 2L * R * sm.nx > 16384) --R;
+  const long rpp = (long)sm.nz * sm.ny;
+  const long wpp = (rpp + R - 1) / R;
+  const long nwg = wpp * npatch;
+  const int thr = threads_for_tf(2L * R * sm.nx);
+  const size_t lds = (size_t)(sm.nx + 2 * R * sm.nx) * sizeof(float2);
+  { ScopedTiming _t("k_tf_rows_lf", s);
+  hipLaunchKernelGGL(k_tf_rows_lf, dim3((unsigned)nwg), dim3(thr), lds, s, opt, sm, ab, out,
+                     patch_stride, pstride, zstride, R, wpp, plan); }
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ rows: fluorescence
+
+// h: [patch][z][y][x] complex (after the inverse Y pass); out: [patch][z][y][Xh]
+__global__ __launch_bounds__(1024) void k_tf_rows_fl(const DevOptics* __restrict__ opt,
+                                                     Sampling sm, const float2* __restrict__ h,
+                                                     float2* __restrict__ out, int pairs_per_wg,
+                                                     long wg_per_patch, FftPlan plan) {
+  extern __shared__ float2 smem[];
+  const int Y = sm.ny, X = sm.nx, Z = sm.nz, Xh = X / 2 + 1;
+  float2* tw = smem;
+  float2* buf = smem + X;
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  fill_twiddles(tw, X, tid, nthr);
+  const long patch = blockIdx.x / wg_per_patch;
+  const long rpp = (long)Z * Y;
+  const long row0 = (blockIdx.x - patch * wg_per_patch) * 2L * pairs_per_wg;
+  const int nrows = (int)min(2L * pairs_per_wg, rpp - row0);
+  const int np = (nrows + 1) / 2;
+  const float2* src = h + patch * rpp * X;
+  for (int e = tid; e < 2 * np * X; e += nthr) {
+    const int l = e / X, i = e - l * X;
+    buf[e] = l < nrows ? src[(row0 + l) * X + i] : make_float2(0.f, 0.f);
+  }
+  __syncthreads();
+  lds_fft(buf, LdsLines{2 * np, 1, X, false}, plan, tw, 1.f, tid, nthr);
+  const double norm = 1.0 / ((double)Z * (double)X * (double)Y * opt[patch].ibg);
+  const float nm = (float)norm;
+  for (int e = tid; e < np * X; e += nthr) {
+    const int q = e / X, i = e - q * X;
+    const float2 u = buf[2 * q * X + i], v = buf[(2 * q + 1) * X + i];
+    buf[2 * q * X + i] = make_float2((u.x * u.x + u.y * u.y) * nm, (v.x * v.x + v.y * v.y) * nm);
+  }
+  __syncthreads();
+  lds_fft(buf, LdsLines{np, 1, 2 * X, false}, plan, tw, -1.f, tid, nthr);
+  float2* op = out + patch * rpp * Xh;
+  for (int e = tid; e < np * Xh; e += nthr) {
+    const int q = e / Xh, k = e - q * Xh;
+    const float2 zk = buf[2 * q * X + k];
+    const float2 zm = buf[2 * q * X + (k == 0 ? 0 : X - k)];
+    const long r0 = row0 + 2 * q;
+    op[r0 * Xh + k] = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y));
+    if (r0 + 1 < rpp && 2 * q + 1 < nrows)
+      op[(r0 + 1) * Xh + k] = make_float2(0.5f * (zk.y + zm.y), -0.5f * (zk.x - zm.x));
+  }
+}
+
+hipError_t launch_tf_rows_fluor(const DevOptics* opt, const Sampling& sm, int npatch,
+                                const float2* h, float2* out, hipStream_t s) {
+  FftPlan plan;
+  if (!make_plan(sm.nx, &plan)) return hipErrorInvalidValue;
+  int Q = 2048 / sm.nx;                       // row pairs per workgroup
+  if (Q < 1) Q = 1;
+  while (Q > 1 && 2L * Q * sm.nx > 16384) --Q;
+  const long rpp = (long)sm.nz * sm.ny;
+  const long wpp = (rpp + 2 * Q - 1) / (2 * Q);
+  const long nwg = wpp * npatch;
+  const int thr = threads_for_tf(2L * Q * sm.nx);
+  const size_t lds = (size_t)(sm.nx + 2 * Q * sm.nx) * sizeof(float2);
+  { ScopedTiming _t("k_tf_rows_fl", s);
+  hipLaunchKernelGGL(k_tf_rows_fl, dim3((unsigned)nwg), dim3(thr), lds, s, opt, sm, h, out, Q,
+                     wpp, plan); }
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ polarisation bank, Z pass
+
+// uw: [patch][2][Z][M] (phase, absorption half spectra after the Y pass);
+// tf: [patch][5][4][Z][M], H_cp = Re(kappa_cp) U + Im(kappa_cp) V after the Z transform.
+__global__ __launch_bounds__(1024) void k_tf_pol5_z(const DevOptics* __restrict__ opt, int Z,
+                                                    long M, const float2* __restrict__ uw,
+                                                    float2* __restrict__ tf, int W, long tiles_m,
+                                                    FftPlan plan) {
+  extern __shared__ float2 smem[];
+  float2* tw = smem;
+  float2* buf = smem + Z;
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  fill_twiddles(tw, Z, tid, nthr);
+  const long tile = blockIdx.x % tiles_m;
+  const long patch = blockIdx.x / tiles_m;
+  const long m0 = tile * W;
+  const int weff = (int)min((long)W, M - m0);
+  const float2* src = uw + patch * 2L * Z * M;
+  for (int e = tid; e < 2 * Z * W; e += nthr) {
+    const int w = e % W;
+    const int t = e / W;
+    const int z = t % Z, f = t / Z;
+    buf[(z * 2 + f) * W + w] = w < weff ? src[((long)f * Z + z) * M + m0 + w] : make_float2(0.f, 0.f);
+  }
+  __syncthreads();
+  lds_fft(buf, LdsLines{2 * W, 2 * W, 1, true}, plan, tw, -1.f, tid, nthr);
+  float kr[20], ki[20];
+  const DevOptics& o = opt[patch];
+#pragma unroll
+  for (int j = 0; j < 20; ++j) {
+    kr[j] = (float)o.kappa[j / 4][j % 4][0];
+    ki[j] = (float)o.kappa[j / 4][j % 4][1];
+  }
+  float2* dst = tf + patch * 20L * Z * M;
+  for (int e = tid; e < Z * W; e += nthr) {
+    const int z = e / W, w = e - z * W;
+    if (w >= weff) continue;
+    const float2 u = buf[(z * 2) * W + w], v = buf[(z * 2 + 1) * W + w];
+#pragma unroll
+    for (int j = 0; j < 20; ++j)
+      dst[((long)j * Z + z) * M + m0 + w] =
+          make_float2(kr[j] * u.x + ki[j] * v.x, kr[j] * u.y + ki[j] * v.y);
+  }
+}
+
+hipError_t launch_tf_pol5_z(const DevOptics* opt, const Sampling& sm, int npatch, float2* uw,
+                            float2* tf, hipStream_t s) {
+  FftPlan plan;
+  if (!make_plan(sm.nz, &plan)) return hipErrorInvalidValue;
+  const long M = (long)sm.ny * (sm.nx / 2 + 1);
+  const long lim = lds_limit_bytes() / (long)sizeof(float2);
+  int W = 16;
+  while (W > 1 && (2L * W * sm.nz > 16384 || sm.nz + 2L * W * sm.nz > lim)) W /= 2;
+  const long tiles = (M + W - 1) / W;
+  const long nwg = tiles * npatch;
+  const int thr = threads_for_tf(2L * sm.nz * W);
+  const size_t lds = (size_t)(sm.nz + 2 * sm.nz * W) * sizeof(float2);
+  { ScopedTiming _t("k_tf_pol5_z", s);
+  hipLaunchKernelGGL(k_tf_pol5_z, dim3((unsigned)nwg), dim3(thr), lds, s, opt, sm.nz, M, uw, tf, W,
+                     tiles, plan); }
+  return hipGetLastError();
+}
+
+}  // namespace wo

@@ -1,0 +1,87 @@
+"""The C-ABI library loads and exports every symbol the header declares (CPU only).
+
+No compute call is made here: the calls below fail argument validation,
+which happens on the host before anything is enqueued on a GPU.
+"""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2412_09775_amd import api
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "waveorder.h")
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?[\w\*\s]+?\b(wo_\w+)\s*\(", text, re.M)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(api.LIB_PATH):
+        pytest.fail("libwaveorder.so is not built (run __graft_entry__.build())")
+    return api.load()
+
+
+def test_header_declares_the_abi():
+    syms = declared_symbols()
+    for s in ("wo_transfer_function", "wo_forward", "wo_reconstruct", "wo_adjoint",
+              "wo_workspace_size", "wo_bank_shape", "wo_strerror", "wo_version"):
+        assert s in syms
+
+
+def test_library_exports_every_declared_symbol(lib):
+    for s in declared_symbols():
+        assert hasattr(lib, s), s
+    assert set(api.SYMBOLS) == set(declared_symbols())
+
+
+def _optics(**kw):
+    base = dict(model=api.MODEL_LABELFREE_3D, nz=32, ny=64, nx=64, dz=0.2, dy=0.1, dx=0.1,
+                wavelength=0.532, na_ill=0.5, na_det=1.2, n_medium=1.33)
+    base.update(kw)
+    return api.Optics(**base)
+
+
+def test_bank_shape_and_workspace(lib):
+    assert api.bank_shape(_optics()) == (1, 2, 3, 2 * 32 * 64 * 33)
+    assert api.bank_shape(_optics(model=api.MODEL_POL5_3D, na_det=0.75))[:3] == (5, 4, 3)
+    assert api.bank_shape(_optics(model=api.MODEL_LABELFREE_THIN))[:3] == (32, 2, 2)
+    assert api.bank_shape(_optics(model=api.MODEL_FLUOR_3D))[:3] == (1, 1, 3)
+    ws = api.workspace_size(_optics(), api.OP_RECONSTRUCT)
+    assert ws >= 2 * 32 * 64 * 33 * 8
+    assert api.workspace_size([_optics()] * 3, api.OP_RECONSTRUCT) >= 3 * 2 * 32 * 64 * 33 * 8
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(na_det=1.4), -1),                 # pupil beyond the shell n / lambda0
+    (dict(dx=0.2, dy=0.2), -5),             # lateral aliasing
+    (dict(dz=0.5), -5),                     # axial aliasing
+    (dict(nx=70), -2),                      # 7 is not a supported radix
+    (dict(ny=45), -2),                      # odd size
+    (dict(wavelength=-1.0), -1),
+    (dict(tilt_zenith=1.2), -1),            # tilted source leaves the shell
+])
+def test_invalid_optics_are_rejected_before_any_gpu_work(lib, kw, status):
+    arr = api.optics_array(_optics(**kw))
+    st = lib.wo_transfer_function(arr, 1, ctypes.c_void_p(1), ctypes.c_void_p(1), 1 << 40, None)
+    assert st == status
+
+
+def test_null_and_small_workspace_are_rejected(lib):
+    arr = api.optics_array(_optics())
+    assert lib.wo_transfer_function(arr, 1, None, None, 0, None) == -1
+    assert lib.wo_transfer_function(arr, 1, ctypes.c_void_p(1), ctypes.c_void_p(1), 16, None) == -3
+    assert lib.wo_reconstruct(arr, 1, ctypes.c_void_p(1), ctypes.c_void_p(1), None, -1.0,
+                              ctypes.c_void_p(1), ctypes.c_void_p(1), 1 << 40, None) == -1
+    assert lib.wo_reconstruct(arr, 1, ctypes.c_void_p(1), ctypes.c_void_p(1), None, 0.0,
+                              ctypes.c_void_p(1), ctypes.c_void_p(1), 1 << 40, None) == -2
+    mixed = api.optics_array([_optics(), _optics(nz=16)])
+    assert lib.wo_forward(mixed, 2, ctypes.c_void_p(1), ctypes.c_void_p(1), None,
+                          ctypes.c_void_p(1), ctypes.c_void_p(1), 1 << 40, None) == -1
+    assert lib.wo_strerror(-5).decode().startswith("transfer-function support")
