@@ -224,9 +224,15 @@ Sampling sampling_of(const wo_optics* o) {
 
 size_t params_bytes(int32_t n) { return align_up((size_t)n * sizeof(DevOptics)); }
 
+size_t partials_bytes(const wo_optics* o, int32_t n) {
+  const Sampling sm = sampling_of(o);
+  const int W = tf_tile_width(sm);
+  return align_up((size_t)n * ((o->nx + W - 1) / W) * sizeof(double));
+}
+
 size_t tf_ws(const wo_optics* o, int32_t n, const Shape& s) {
   const int nf = o->model == WO_MODEL_FLUOR_3D ? 1 : 2;
-  size_t b = params_bytes(n);
+  size_t b = params_bytes(n) + partials_bytes(o, n);
   b += align_up((size_t)n * nf * s.Z * s.Y * s.X * sizeof(float2));
   if (o->model == WO_MODEL_POL5_3D) b += align_up((size_t)n * 2 * s.Z * s.Y * s.Xh * sizeof(float2));
   return b;
@@ -375,34 +381,35 @@ int wo_transfer_function(const wo_optics* o, int32_t n, void* tf_out, void* ws, 
   char* w = (char*)ws;
   DevOptics* dopt = (DevOptics*)w;
   w += params_bytes(n);
+  double* partials = (double*)w;
+  w += partials_bytes(o, n);
   const int nf = o->model == WO_MODEL_FLUOR_3D ? 1 : 2;
   float2* ab = (float2*)w;
   w += align_up((size_t)n * nf * s.Z * s.Y * s.X * sizeof(float2));
   WO_TRY(launch_set_params(dopt, h.data(), n, hs));
   const Sampling sm = sampling_of(o);
-  WO_TRY(launch_pupil_sums(dopt, sm, n, hs));
-  WO_TRY(launch_tf_fields_y(dopt, sm, n, ab, hs));
+  WO_TRY(launch_tf_fields_y(dopt, sm, n, ab, partials, hs));
   float2* tf = (float2*)tf_out;
   const long M = s.Y * s.Xh;
   const long plane = s.Y * s.Xh;
   switch (o->model) {
     case WO_MODEL_FLUOR_3D:
-      WO_TRY(launch_tf_rows_fluor(dopt, sm, n, ab, tf, hs));
+      WO_TRY(launch_tf_rows_fluor(partials, sm, n, ab, tf, hs));
       WO_TRY(launch_cols(tf, (int)s.Y, s.Xh, s.Z, s.Z, n, -1.f, hs, "k_cols_y_tf"));
       WO_TRY(launch_cols(tf, (int)s.Z, M, 1, 1, n, -1.f, hs, "k_cols_z_tf"));
       break;
     case WO_MODEL_LABELFREE_3D:
-      WO_TRY(launch_tf_rows_labelfree(dopt, sm, n, ab, tf, 2 * s.Z * plane, s.Z * plane, plane, hs));
+      WO_TRY(launch_tf_rows_labelfree(partials, sm, n, ab, tf, 2 * s.Z * plane, s.Z * plane, plane, hs));
       WO_TRY(launch_cols(tf, (int)s.Y, s.Xh, 2 * s.Z, 2 * s.Z, n, -1.f, hs, "k_cols_y_tf"));
       WO_TRY(launch_cols(tf, (int)s.Z, M, 2, 2, n, -1.f, hs, "k_cols_z_tf"));
       break;
     case WO_MODEL_LABELFREE_THIN:
-      WO_TRY(launch_tf_rows_labelfree(dopt, sm, n, ab, tf, 2 * s.Z * plane, plane, 2 * plane, hs));
+      WO_TRY(launch_tf_rows_labelfree(partials, sm, n, ab, tf, 2 * s.Z * plane, plane, 2 * plane, hs));
       WO_TRY(launch_cols(tf, (int)s.Y, s.Xh, 2 * s.Z, 2 * s.Z, n, -1.f, hs, "k_cols_y_tf"));
       break;
     case WO_MODEL_POL5_3D: {
       float2* uw = (float2*)w;
-      WO_TRY(launch_tf_rows_labelfree(dopt, sm, n, ab, uw, 2 * s.Z * plane, s.Z * plane, plane, hs));
+      WO_TRY(launch_tf_rows_labelfree(partials, sm, n, ab, uw, 2 * s.Z * plane, s.Z * plane, plane, hs));
       WO_TRY(launch_cols(uw, (int)s.Y, s.Xh, 2 * s.Z, 2 * s.Z, n, -1.f, hs, "k_cols_y_tf"));
       WO_TRY(launch_tf_pol5_z(dopt, sm, n, uw, tf, hs));
       break;

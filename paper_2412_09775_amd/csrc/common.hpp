@@ -16,26 +16,49 @@
 namespace wo {
 
 constexpr int kMaxPasses = 16;
-constexpr int kEmax = 16;          // elements owned by one thread in an LDS FFT
+constexpr int kEmax = 8;                   // elements owned by one thread in an LDS FFT
+constexpr int kMaxThreads = 1024;
+constexpr int kMaxElems = kEmax * kMaxThreads;  // elements one workgroup may own
 
+// Threads for a workgroup owning `elems` elements: a multiple of 64 with
+// threads * kEmax >= elems (callers keep elems <= kMaxElems).
+inline int threads_for(long elems) {
+  long t = (elems + kEmax - 1) / kEmax;
+  t = ((t + 63) / 64) * 64;
+  if (t < 64) t = 64;
+  if (t > kMaxThreads) t = kMaxThreads;
+  return (int)t;
+}
+
+// Radix sequence of one transform length, packed 4 bits per pass (the radix
+// itself) so that device code reads it with shifts instead of indexing an
+// array (which would force the plan into private memory).
 struct FftPlan {
   int n;
   int npass;
-  int radix[kMaxPasses];
+  unsigned long long radices;
 };
+
+__host__ __device__ inline int plan_radix(const FftPlan& p, int q) {
+  return (int)((p.radices >> (4 * q)) & 15ull);
+}
 
 // Host-side factorisation: as many radix-8 passes as possible, then 4, 2, 3, 5.
 // Returns false when n has a prime factor other than 2, 3, 5.
 inline bool make_plan(int n, FftPlan* p) {
   p->n = n;
   p->npass = 0;
+  p->radices = 0;
   int m = n;
   if (n < 1) return false;
-  while (m % 8 == 0 && p->npass < kMaxPasses) { p->radix[p->npass++] = 8; m /= 8; }
-  while (m % 4 == 0 && p->npass < kMaxPasses) { p->radix[p->npass++] = 4; m /= 4; }
-  while (m % 2 == 0 && p->npass < kMaxPasses) { p->radix[p->npass++] = 2; m /= 2; }
-  while (m % 3 == 0 && p->npass < kMaxPasses) { p->radix[p->npass++] = 3; m /= 3; }
-  while (m % 5 == 0 && p->npass < kMaxPasses) { p->radix[p->npass++] = 5; m /= 5; }
+  const int order[5] = {8, 4, 2, 3, 5};
+  for (int f : order) {
+    while (m % f == 0 && p->npass < kMaxPasses) {
+      p->radices |= (unsigned long long)f << (4 * p->npass);
+      p->npass++;
+      m /= f;
+    }
+  }
   return m == 1;
 }
 
@@ -141,6 +164,41 @@ __device__ __forceinline__ void fill_twiddles(float2* tw, int n, int tid, int nt
   }
 }
 
+// Cooperative copy of `total` (<= kEmax * nthr) elements into LDS, element e
+// taken from src(e).  Every load of a thread is issued before its LDS stores,
+// so the loads of one thread are in flight together.
+template <typename F>
+__device__ __forceinline__ void gather_to_lds(float2* buf, int total, int tid, int nthr, F src) {
+  float2 t[kEmax];
+#pragma unroll
+  for (int i = 0; i < kEmax; ++i) {
+    const int e = tid + i * nthr;
+    if (e < total) t[i] = src(e);
+  }
+#pragma unroll
+  for (int i = 0; i < kEmax; ++i) {
+    const int e = tid + i * nthr;
+    if (e < total) buf[e] = t[i];
+  }
+}
+
+// Cooperative write-out of `total` (<= kEmax * nthr) elements: dst(e, value).
+template <typename F>
+__device__ __forceinline__ void scatter_from_lds(const float2* buf, int total, int tid, int nthr,
+                                                 F dst) {
+  float2 t[kEmax];
+#pragma unroll
+  for (int i = 0; i < kEmax; ++i) {
+    const int e = tid + i * nthr;
+    if (e < total) t[i] = buf[e];
+  }
+#pragma unroll
+  for (int i = 0; i < kEmax; ++i) {
+    const int e = tid + i * nthr;
+    if (e < total) dst(e, t[i]);
+  }
+}
+
 // Line layout in LDS: element i of line l lives at lds[line_base(l) + i * es].
 // linefast == true maps consecutive butterfly slots to consecutive lines
 // (use when lines are adjacent in LDS, es = number of lines); otherwise
@@ -205,7 +263,7 @@ __device__ __forceinline__ void lds_fft(float2* lds, const LdsLines L, const Fft
                                         const float2* tw, float s, int tid, int nthr) {
   int ns = 1;
   for (int q = 0; q < p.npass; ++q) {
-    const int R = p.radix[q];
+    const int R = plan_radix(p, q);
     switch (R) {
       case 8: stockham_pass<8>(lds, L, p.n, ns, tw, s, tid, nthr); break;
       case 4: stockham_pass<4>(lds, L, p.n, ns, tw, s, tid, nthr); break;

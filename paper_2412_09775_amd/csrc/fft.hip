@@ -10,14 +10,6 @@
 
 namespace wo {
 
-static int threads_for(long elems) {
-  long t = (elems + kEmax - 1) / kEmax;
-  t = ((t + 63) / 64) * 64;
-  if (t < 64) t = 64;
-  if (t > 1024) t = 1024;
-  return (int)t;
-}
-
 // ------------------------------------------------------------------ rows
 
 __device__ __forceinline__ long group_row(long r, long rpg, long stride) {
@@ -43,23 +35,27 @@ __global__ __launch_bounds__(1024) void k_rows_r2c(const float* __restrict__ in,
     rout[t] = r < nrows ? group_row(r, g.rows_per_group, g.out_stride) : -1;
   }
   __syncthreads();
-  for (int e = tid; e < nl * X; e += nthr) {
+  gather_to_lds(buf, nl * X, tid, nthr, [&](int e) {
     const int l = e / X, i = e - l * X;
     const float a = in[rin[2 * l] * X + i];
     const float b = rin[2 * l + 1] >= 0 ? in[rin[2 * l + 1] * X + i] : 0.f;
-    buf[e] = make_float2(a, b);
-  }
+    return make_float2(a, b);
+  });
   __syncthreads();
   lds_fft(buf, LdsLines{nl, 1, X, false}, plan, tw, -1.f, tid, nthr);
   const int Xh = X / 2 + 1;
-  for (int e = tid; e < nl * Xh; e += nthr) {
-    const int l = e / Xh, k = e - l * Xh;
-    const float2 zk = buf[l * X + k];
-    const float2 zm = buf[l * X + (k == 0 ? 0 : X - k)];
-    const float2 A = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y));
-    const float2 B = make_float2(0.5f * (zk.y + zm.y), -0.5f * (zk.x - zm.x));
-    out[rout[2 * l] * Xh + k] = A;
-    if (rout[2 * l + 1] >= 0) out[rout[2 * l + 1] * Xh + k] = B;
+#pragma unroll
+  for (int i = 0; i < kEmax; ++i) {
+    const int e = tid + i * nthr;
+    if (e < nl * Xh) {
+      const int l = e / Xh, k = e - l * Xh;
+      const float2 zk = buf[l * X + k];
+      const float2 zm = buf[l * X + (k == 0 ? 0 : X - k)];
+      const float2 A = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y));
+      const float2 B = make_float2(0.5f * (zk.y + zm.y), -0.5f * (zk.x - zm.x));
+      out[rout[2 * l] * Xh + k] = A;
+      if (rout[2 * l + 1] >= 0) out[rout[2 * l + 1] * Xh + k] = B;
+    }
   }
 }
 
@@ -83,7 +79,7 @@ __global__ __launch_bounds__(1024) void k_rows_c2r(const float2* __restrict__ in
   }
   __syncthreads();
   const int Xh = X / 2 + 1;
-  for (int e = tid; e < nl * X; e += nthr) {
+  gather_to_lds(buf, nl * X, tid, nthr, [&](int e) {
     const int l = e / X, k = e - l * X;
     const bool mirror = 2 * k > X;
     const int kk = mirror ? X - k : k;
@@ -91,23 +87,22 @@ __global__ __launch_bounds__(1024) void k_rows_c2r(const float2* __restrict__ in
     float2 B = rin[2 * l + 1] >= 0 ? in[rin[2 * l + 1] * Xh + kk] : make_float2(0.f, 0.f);
     if (kk == 0 || 2 * kk == X) { A.y = 0.f; B.y = 0.f; }   // Re of the inverse ignores them
     if (mirror) { A.y = -A.y; B.y = -B.y; }
-    buf[e] = make_float2(A.x - B.y, A.y + B.x);
-  }
+    return make_float2(A.x - B.y, A.y + B.x);
+  });
   __syncthreads();
   lds_fft(buf, LdsLines{nl, 1, X, false}, plan, tw, 1.f, tid, nthr);
-  for (int e = tid; e < nl * X; e += nthr) {
+  scatter_from_lds(buf, nl * X, tid, nthr, [&](int e, float2 v) {
     const int l = e / X, i = e - l * X;
-    const float2 v = buf[e];
     out[rout[2 * l] * X + i] = v.x * scale;
     if (rout[2 * l + 1] >= 0) out[rout[2 * l + 1] * X + i] = v.y * scale;
-  }
+  });
 }
 
 static int lines_per_wg_for(int X) {
   int L = 4096 / X;
   if (L < 1) L = 1;
   if (L > 64) L = 64;
-  while (L > 1 && (long)L * X > 16384) --L;
+  while (L > 1 && (long)L * X > kMaxElems) --L;
   return L;
 }
 
@@ -159,16 +154,16 @@ __global__ __launch_bounds__(1024) void k_cols(float2* __restrict__ data, int N,
   float2* base = data + (pg * group_stride + pi) * (long)N * M;
   const long m0 = tile * W;
   const int weff = (int)min((long)W, M - m0);
-  for (int e = tid; e < N * W; e += nthr) {
+  gather_to_lds(buf, N * W, tid, nthr, [&](int e) {
     const int n = e / W, w = e - n * W;
-    buf[e] = w < weff ? base[(long)n * M + m0 + w] : make_float2(0.f, 0.f);
-  }
+    return w < weff ? base[(long)n * M + m0 + w] : make_float2(0.f, 0.f);
+  });
   __syncthreads();
   lds_fft(buf, LdsLines{W, W, 1, true}, plan, tw, sign, tid, nthr);
-  for (int e = tid; e < N * W; e += nthr) {
+  scatter_from_lds(buf, N * W, tid, nthr, [&](int e, float2 v) {
     const int n = e / W, w = e - n * W;
-    if (w < weff) base[(long)n * M + m0 + w] = buf[e];
-  }
+    if (w < weff) base[(long)n * M + m0 + w] = v;
+  });
 }
 
 // Column tile width: W contiguous complex values per row (W = 16 is one
@@ -177,7 +172,7 @@ __global__ __launch_bounds__(1024) void k_cols(float2* __restrict__ data, int N,
 static int tile_width(int n, int ch) {
   const long lim = lds_limit_bytes() / (long)sizeof(float2);
   int W = 16;
-  while (W > 1 && ((long)W * n * ch > 16384 || n + (long)W * n * ch > lim)) W /= 2;
+  while (W > 1 && ((long)W * n * ch > kMaxElems || n + (long)W * n * ch > lim)) W /= 2;
   return W;
 }
 
@@ -198,18 +193,20 @@ hipError_t launch_cols(float2* data, int N, long M, long planes_per_group, long 
 
 // ------------------------------------------------------------------ per-frequency operators
 //
-// Channel values of one frequency sit at cell[ch * cs].  tfp points at the
-// (c = 0, p = 0) TF value of this frequency; entry (c, p) is at tfp[(c*P+p)*ts].
+// Channel values of one frequency sit at cell[ch * cs].  H(c, p) returns the
+// transfer-function value of channel c and property p at this frequency.
 // forward: y_c = sum_p H_cp x_p (+ N b_c at DC)
 // solve:   F = (H^H H + eta I)^-1 H^H (x - N b delta)      (Eq. tls_solution)
 // adjoint: y_p = sum_c conj(H_cp) x_c
 // Outputs are scaled by inv_n (the 1/N of the inverse transform).
 
-template <int P>
-__device__ __forceinline__ void freq_op(float2* cell, long cs, const float2* __restrict__ tfp,
-                                        long ts, int C, int mode, float eta,
+// CT > 0 fixes the channel count at compile time (static register indexing);
+// CT == 0 takes it from Crt.
+template <int P, int CT, typename HF>
+__device__ __forceinline__ void freq_op(float2* cell, long cs, HF H, int Crt, int mode, float eta,
                                         const float* __restrict__ bg, bool dc, float n_full,
                                         float inv_n) {
+  const int C = CT > 0 ? CT : Crt;
   if (mode == kModeForward) {
     float2 x[P];
 #pragma unroll
@@ -217,7 +214,7 @@ __device__ __forceinline__ void freq_op(float2* cell, long cs, const float2* __r
     for (int c = 0; c < C; ++c) {
       float2 y = make_float2(0.f, 0.f);
 #pragma unroll
-      for (int p = 0; p < P; ++p) y = cadd(y, cmul(tfp[(long)(c * P + p) * ts], x[p]));
+      for (int p = 0; p < P; ++p) y = cadd(y, cmul(H(c, p), x[p]));
       if (dc && bg) y.x += n_full * bg[c];
       cell[c * cs] = cscale(y, inv_n);
     }
@@ -230,13 +227,14 @@ __device__ __forceinline__ void freq_op(float2* cell, long cs, const float2* __r
     for (int c = 0; c < C; ++c) {
       const float2 xc = cell[c * cs];
 #pragma unroll
-      for (int p = 0; p < P; ++p) y[p] = cadd(y[p], cmul(cconj(tfp[(long)(c * P + p) * ts]), xc));
+      for (int p = 0; p < P; ++p) y[p] = cadd(y[p], cmul(cconj(H(c, p)), xc));
     }
 #pragma unroll
     for (int p = 0; p < P; ++p) cell[p * cs] = cscale(y[p], inv_n);
     return;
   }
-  // solve: accumulate the P x P normal matrix (lower triangle) and H^H x
+  // solve: accumulate the lower triangle of M = H^H H, M_pq = sum_c conj(H_cp) H_cq,
+  // and r = H^H x
   float2 m[P][P];
   float2 r[P];
 #pragma unroll
@@ -250,7 +248,7 @@ __device__ __forceinline__ void freq_op(float2* cell, long cs, const float2* __r
     if (dc && bg) xc.x -= n_full * bg[c];
     float2 h[P];
 #pragma unroll
-    for (int p = 0; p < P; ++p) h[p] = tfp[(long)(c * P + p) * ts];
+    for (int p = 0; p < P; ++p) h[p] = H(c, p);
 #pragma unroll
     for (int p = 0; p < P; ++p) {
       r[p] = cadd(r[p], cmul(cconj(h[p]), xc));
@@ -258,13 +256,12 @@ __device__ __forceinline__ void freq_op(float2* cell, long cs, const float2* __r
       for (int q = 0; q <= p; ++q) m[p][q] = cadd(m[p][q], cmul(cconj(h[p]), h[q]));
     }
   }
-  // m[p][q] (p >= q) holds the lower triangle of M = H^H H, M_pq = sum_c conj(H_cp) H_cq.
   float2 F[P];
   if (P == 1) {
     const float den = m[0][0].x + eta;
     F[0] = den > 0.f ? cscale(r[0], 1.f / den) : make_float2(0.f, 0.f);
   } else {
-    // Cholesky M = L L^H with M_pq (p >= q) = m[p][q]
+    // Cholesky M + eta I = L L^H, then two triangular solves
     float2 L[P][P];
     float dinv[P];
 #pragma unroll
@@ -302,7 +299,9 @@ __device__ __forceinline__ void freq_op(float2* cell, long cs, const float2* __r
   for (int p = 0; p < P; ++p) cell[p * cs] = cscale(F[p], inv_n);
 }
 
-template <int P>
+constexpr int kTfPrefetch = 8;   // transfer-function values a thread may hold in registers
+
+template <int P, int CT>
 __global__ __launch_bounds__(1024) void k_zop(float2* __restrict__ spec,
                                               const float2* __restrict__ tf, int C, int Z, long M,
                                               int slots, int W, long tiles_m, FftPlan plan,
@@ -312,7 +311,6 @@ __global__ __launch_bounds__(1024) void k_zop(float2* __restrict__ spec,
   float2* tw = smem;
   float2* buf = smem + Z;
   const int tid = threadIdx.x, nthr = blockDim.x;
-  fill_twiddles(tw, Z, tid, nthr);
   const long bid = blockIdx.x;
   const long tile = bid % tiles_m;
   const long patch = bid / tiles_m;
@@ -324,29 +322,105 @@ __global__ __launch_bounds__(1024) void k_zop(float2* __restrict__ spec,
   const float* bp = bg ? bg + patch * C : nullptr;
   const long m0 = tile * W;
   const int weff = (int)min((long)W, M - m0);
-  for (int e = tid; e < cin * Z * W; e += nthr) {
-    const int w = e % W;
-    const int t = e / W;
-    const int z = t % Z, ch = t / Z;
-    buf[(z * CH + ch) * W + w] = w < weff ? sp[((long)ch * Z + z) * M + m0 + w] : make_float2(0.f, 0.f);
+  const long ts = (long)Z * M;               // stride between (c, p) entries of the bank
+  // Issue this thread's transfer-function loads first: they complete while the
+  // data tile is loaded and transformed.  Frequency f = tid + i * nthr.
+  const int nfreq = Z * W;
+  const int fpt = (nfreq + nthr - 1) / nthr;
+  const bool prefetch = CT == 1 && P * fpt <= kTfPrefetch;
+  float2 hreg[kTfPrefetch];
+  if (prefetch) {
+#pragma unroll
+    for (int j = 0; j < kTfPrefetch; ++j) {
+      const int i = j / P, cp = j - i * P;
+      const int f = tid + i * nthr;
+      if (i < fpt && f < nfreq) {
+        const int z = f / W, w = f - z * W;
+        hreg[j] = w < weff ? tp[cp * ts + (long)z * M + m0 + w] : make_float2(0.f, 0.f);
+      }
+    }
+  }
+  fill_twiddles(tw, Z, tid, nthr);
+  {
+    // element e = (ch, z, w) of the global tile goes to LDS [z][ch][w]
+    float2 t[kEmax];
+#pragma unroll
+    for (int i = 0; i < kEmax; ++i) {
+      const int e = tid + i * nthr;
+      if (e < cin * Z * W) {
+        const int w = e % W, r = e / W;
+        const int z = r % Z, ch = r / Z;
+        t[i] = w < weff ? sp[((long)ch * Z + z) * M + m0 + w] : make_float2(0.f, 0.f);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < kEmax; ++i) {
+      const int e = tid + i * nthr;
+      if (e < cin * Z * W) {
+        const int w = e % W, r = e / W;
+        const int z = r % Z, ch = r / Z;
+        buf[(z * CH + ch) * W + w] = t[i];
+      }
+    }
   }
   __syncthreads();
   lds_fft(buf, LdsLines{cin * W, CH * W, 1, true}, plan, tw, -1.f, tid, nthr);
-  for (int f = tid; f < Z * W; f += nthr) {
-    const int z = f / W, w = f - z * W;
-    if (w >= weff) continue;
-    const long m = m0 + w;
-    freq_op<P>(buf + (long)z * CH * W + w, W, tp + (long)z * M + m, (long)Z * M, C, mode, eta, bp,
-               z == 0 && m == 0, n_full, inv_n);
+  if (prefetch) {
+#pragma unroll
+    for (int i = 0; i < kTfPrefetch; ++i) {
+      const int f = tid + i * nthr;
+      if (i < fpt && f < nfreq) {
+        const int z = f / W, w = f - z * W;
+        if (w < weff) {
+          const long m = m0 + w;
+          freq_op<P, 1>(buf + (long)z * CH * W + w, W,
+                        [&](int c, int p) { return hreg[i * P + p]; }, C, mode, eta, bp,
+                        z == 0 && m == 0, n_full, inv_n);
+        }
+      }
+    }
+  } else {
+    for (int f = tid; f < nfreq; f += nthr) {
+      const int z = f / W, w = f - z * W;
+      if (w >= weff) continue;
+      const long m = m0 + w;
+      const float2* hp = tp + (long)z * M + m;
+      freq_op<P, CT>(buf + (long)z * CH * W + w, W,
+                     [&](int c, int p) { return hp[(long)(c * P + p) * ts]; }, C, mode, eta, bp,
+                     z == 0 && m == 0, n_full, inv_n);
+    }
   }
   __syncthreads();
   lds_fft(buf, LdsLines{cout * W, CH * W, 1, true}, plan, tw, 1.f, tid, nthr);
-  for (int e = tid; e < cout * Z * W; e += nthr) {
-    const int w = e % W;
-    const int t = e / W;
-    const int z = t % Z, ch = t / Z;
-    if (w < weff) sp[((long)ch * Z + z) * M + m0 + w] = buf[(z * CH + ch) * W + w];
+  {
+    float2 t[kEmax];
+#pragma unroll
+    for (int i = 0; i < kEmax; ++i) {
+      const int e = tid + i * nthr;
+      if (e < cout * Z * W) {
+        const int w = e % W, r = e / W;
+        const int z = r % Z, ch = r / Z;
+        t[i] = buf[(z * CH + ch) * W + w];
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < kEmax; ++i) {
+      const int e = tid + i * nthr;
+      if (e < cout * Z * W) {
+        const int w = e % W, r = e / W;
+        const int z = r % Z, ch = r / Z;
+        if (w < weff) sp[((long)ch * Z + z) * M + m0 + w] = t[i];
+      }
+    }
   }
+}
+
+template <int P, int CT>
+static void zop_launch(long nwg, int thr, size_t lds, hipStream_t s, float2* spec, const float2* tf,
+                       int C, int Z, long M, int slots, int W, long tiles, FftPlan plan, int mode,
+                       float eta, const float* bg, float inv_n, float nf) {
+  hipLaunchKernelGGL((k_zop<P, CT>), dim3((unsigned)nwg), dim3(thr), lds, s, spec, tf, C, Z, M, slots,
+                     W, tiles, plan, mode, eta, bg, inv_n, nf);
 }
 
 hipError_t launch_zop(float2* spec, const float2* tf, int C, int P, int Z, long M, int slots,
@@ -363,25 +437,14 @@ hipError_t launch_zop(float2* spec, const float2* tf, int C, int P, int Z, long 
   const int thr = threads_for((long)CH * Z * W);
   const size_t lds = (size_t)(Z + CH * Z * W) * sizeof(float2);
   const float nf = (float)n_full;
-  switch (P) {
-    case 1:
-      { ScopedTiming _t("k_zop<1>", s);
-      hipLaunchKernelGGL(k_zop<1>, dim3((unsigned)nwg), dim3(thr), lds, s, spec, tf, C, Z, M, slots,
-                         W, tiles, plan, mode, eta, bg, inv_n, nf); }
-      break;
-    case 2:
-      { ScopedTiming _t("k_zop<2>", s);
-      hipLaunchKernelGGL(k_zop<2>, dim3((unsigned)nwg), dim3(thr), lds, s, spec, tf, C, Z, M, slots,
-                         W, tiles, plan, mode, eta, bg, inv_n, nf); }
-      break;
-    case 4:
-      { ScopedTiming _t("k_zop<4>", s);
-      hipLaunchKernelGGL(k_zop<4>, dim3((unsigned)nwg), dim3(thr), lds, s, spec, tf, C, Z, M, slots,
-                         W, tiles, plan, mode, eta, bg, inv_n, nf); }
-      break;
-    default:
-      return hipErrorInvalidValue;
-  }
+  ScopedTiming _t(P == 1 ? "k_zop<1>" : (P == 2 ? "k_zop<2>" : "k_zop<4>"), s);
+#define WO_ZOP(PP, CC) \
+  zop_launch<PP, CC>(nwg, thr, lds, s, spec, tf, C, Z, M, slots, W, tiles, plan, mode, eta, bg, inv_n, nf)
+  if (P == 1) { if (C == 1) WO_ZOP(1, 1); else WO_ZOP(1, 0); }
+  else if (P == 2) { if (C == 1) WO_ZOP(2, 1); else WO_ZOP(2, 0); }
+  else if (P == 4) { if (C == 1) WO_ZOP(4, 1); else WO_ZOP(4, 0); }
+  else return hipErrorInvalidValue;
+#undef WO_ZOP
   return hipGetLastError();
 }
 
@@ -397,7 +460,9 @@ __global__ __launch_bounds__(256) void k_op2d(float2* __restrict__ spec,
   float2* sp = spec + patch * (long)slots * M;
   const float2* tp = tf + patch * (long)C * P * M;
   const float* bp = bg ? bg + patch * C : nullptr;
-  freq_op<P>(sp + m, M, tp + m, M, C, mode, eta, bp, m == 0, n_full, inv_n);
+  const float2* hp = tp + m;
+  freq_op<P, 0>(sp + m, M, [&](int c, int p) { return hp[(long)(c * P + p) * M]; }, C, mode, eta,
+                bp, m == 0, n_full, inv_n);
 }
 
 hipError_t launch_op2d(float2* spec, const float2* tf, int C, int P, long M, int slots, int npatch,

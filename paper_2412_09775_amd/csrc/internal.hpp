@@ -60,13 +60,15 @@ hipError_t launch_op2d(float2* spec, const float2* tf, int C, int P, long M, int
 
 // Transfer-function synthesis.
 hipError_t launch_set_params(DevOptics* dst, const DevOptics* host, int n, hipStream_t s);
-hipError_t launch_pupil_sums(DevOptics* opt, const Sampling& sm, int npatch, hipStream_t s);
+// Column tile width of the field kernel; the pupil-sum partials hold
+// ceil(nx / width) doubles per patch.
+int tf_tile_width(const Sampling& sm);
 hipError_t launch_tf_fields_y(const DevOptics* opt, const Sampling& sm, int npatch, float2* ab,
-                              hipStream_t s);
-hipError_t launch_tf_rows_labelfree(const DevOptics* opt, const Sampling& sm, int npatch,
+                              double* partials, hipStream_t s);
+hipError_t launch_tf_rows_labelfree(const double* partials, const Sampling& sm, int npatch,
                                     const float2* ab, float2* out, long patch_stride,
                                     long pstride, long zstride, hipStream_t s);
-hipError_t launch_tf_rows_fluor(const DevOptics* opt, const Sampling& sm, int npatch,
+hipError_t launch_tf_rows_fluor(const double* partials, const Sampling& sm, int npatch,
                                 const float2* h, float2* out, hipStream_t s);
 hipError_t launch_tf_pol5_z(const DevOptics* opt, const Sampling& sm, int npatch, float2* uw,
                             float2* tf, hipStream_t s);

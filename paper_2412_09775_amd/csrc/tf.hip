@@ -13,14 +13,6 @@
 
 namespace wo {
 
-static int threads_for_tf(long elems) {
-  long t = (elems + kEmax - 1) / kEmax;
-  t = ((t + 63) / 64) * 64;
-  if (t < 64) t = 64;
-  if (t > 1024) t = 1024;
-  return (int)t;
-}
-
 // ------------------------------------------------------------------ parameters
 
 // Per-patch optics travel as kernel arguments (a batch of up to 8 records per
@@ -48,47 +40,32 @@ hipError_t launch_set_params(DevOptics* dst, const DevOptics* host, int n, hipSt
   return hipSuccess;
 }
 
-// ------------------------------------------------------------------ pupil sums
+// ------------------------------------------------------------------ reductions
 
-__global__ __launch_bounds__(256) void k_pupil_sums(DevOptics* opt, Sampling sm) {
-  __shared__ double red[256];
-  const int tid = threadIdx.x;
-  const DevOptics o = opt[blockIdx.x];
-  const double hw = soft_halfwidth(o, sm);
-  const double rd = o.na_det / o.wavelength, ri = o.na_ill / o.wavelength;
-  double cy, cx;
-  source_centre(o, &cy, &cx);
-  double acc = 0.0;
-  const long n = (long)sm.ny * sm.nx;
-  for (long idx = tid; idx < n; idx += blockDim.x) {
-    const int ky = (int)(idx / sm.nx), kx = (int)(idx - (long)ky * sm.nx);
-    const double fy = fftfreq(ky, sm.ny, sm.dy), fx = fftfreq(kx, sm.nx, sm.dx);
-    const double P = disc(fy, fx, rd, hw);
-    if (sm.model == kFluor3D) acc += P * P;
-    else acc += disc(fy - cy, fx - cx, ri, hw) * P * P;
-  }
-  red[tid] = acc;
+// Deterministic workgroup sum of one double per thread (wave shuffles, then
+// the wave partials in order).  Result valid in thread 0.
+__device__ __forceinline__ double block_sum(double v, double* red) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (lane == 0) red[wave] = v;
   __syncthreads();
-  for (int st = 128; st > 0; st >>= 1) {
-    if (tid < st) red[tid] += red[tid + st];
-    __syncthreads();
-  }
-  if (tid == 0) opt[blockIdx.x].ibg = red[0];
-}
-
-hipError_t launch_pupil_sums(DevOptics* opt, const Sampling& sm, int npatch, hipStream_t s) {
-  { ScopedTiming _t("k_pupil_sums", s);
-  hipLaunchKernelGGL(k_pupil_sums, dim3(npatch), dim3(256), 0, s, opt, sm); }
-  return hipGetLastError();
+  double t = 0.0;
+  if (threadIdx.x == 0)
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += red[w];
+  return t;
 }
 
 // ------------------------------------------------------------------ fields, inverse Y
 
 // ab layout: [patch][field][z][y][x] complex (field 0 = A or the fluorescence
-// field, field 1 = B).
+// field, field 1 = B).  Workgroups of plane 0 also write the tile's share of
+// the pupil sum (sum S P^2 for label-free, sum P^2 for fluorescence) to
+// partials[patch * tiles_x + tile].
 __global__ __launch_bounds__(1024) void k_tf_fields_y(const DevOptics* __restrict__ opt,
-                                                      Sampling sm, float2* __restrict__ ab, int W,
+                                                      Sampling sm, float2* __restrict__ ab,
+                                                      double* __restrict__ partials, int W,
                                                       long tiles_x, FftPlan plan) {
+  __shared__ double red[kMaxThreads / 64];
   extern __shared__ float2 smem[];
   const int Y = sm.ny, X = sm.nx, Z = sm.nz;
   float2* tw = smem;
@@ -110,6 +87,7 @@ __global__ __launch_bounds__(1024) void k_tf_fields_y(const DevOptics* __restric
   source_centre(o, &cy, &cx);
   const double dzr = plane_z(z, sm) - o.defocus;
   const int x0 = (int)(tile * W);
+  double psum = 0.0;
   for (int e = tid; e < Y * W; e += nthr) {
     const int ky = e / W, w = e - ky * W;
     const int kx = x0 + w;
@@ -119,12 +97,19 @@ __global__ __launch_bounds__(1024) void k_tf_fields_y(const DevOptics* __restric
       const double P = disc(fy, fx, rd, hw);
       if (P != 0.0) {
         const double kz = sqrt(fmax(km * km - (fy * fy + fx * fx), 0.0));
-        double sn, cs;
-        sincospi(2.0 * kz * dzr, &sn, &cs);
+        // phase 2 pi kz (z - dz0): reduce the argument (in units of pi) in FP64 to
+        // [-1, 1], then evaluate sin/cos in FP32
+        const double arg = 2.0 * kz * dzr;
+        const float red = (float)(arg - 2.0 * rint(0.5 * arg));
+        float snf, csf;
+        sincospif(red, &snf, &csf);
+        const double sn = snf, cs = csf;
         if (fluor) {
           A = make_float2((float)(P * cs), (float)(P * sn));
+          psum += P * P;
         } else {
           const double S = disc(fy - cy, fx - cx, ri, hw);
+          psum += S * P * P;
           A = make_float2((float)(S * P * cs), (float)(S * P * sn));
           if (kz > 0.0) {
             const double g = P * km / kz;          // P * (i k_m / kz) * e^{i phi}
@@ -136,43 +121,61 @@ __global__ __launch_bounds__(1024) void k_tf_fields_y(const DevOptics* __restric
     buf[ky * nf * W + w] = A;
     if (!fluor) buf[ky * nf * W + W + w] = B;
   }
+  if (z == 0) {
+    const double tot = block_sum(psum, red);
+    if (tid == 0) partials[patch * tiles_x + tile] = tot;
+  }
   __syncthreads();
   lds_fft(buf, LdsLines{nf * W, nf * W, 1, true}, plan, tw, 1.f, tid, nthr);
-  for (int e = tid; e < Y * nf * W; e += nthr) {
+  scatter_from_lds(buf, Y * nf * W, tid, nthr, [&](int e, float2 v) {
     const int ky = e / (nf * W);
     const int r = e - ky * nf * W;
     const int f = r / W, w = r - f * W;
     const int kx = x0 + w;
-    if (kx < X) ab[(((patch * nf + f) * Z + z) * (long)Y + ky) * X + kx] = buf[e];
-  }
+    if (kx < X) ab[(((patch * nf + f) * Z + z) * (long)Y + ky) * X + kx] = v;
+  });
 }
 
-hipError_t launch_tf_fields_y(const DevOptics* opt, const Sampling& sm, int npatch, float2* ab,
-                              hipStream_t s) {
-  FftPlan plan;
-  if (!make_plan(sm.ny, &plan)) return hipErrorInvalidValue;
+int tf_tile_width(const Sampling& sm) {
   const int nf = sm.model == kFluor3D ? 1 : 2;
   const long lim = lds_limit_bytes() / (long)sizeof(float2);
   int W = 16;
-  while (W > 1 && ((long)W * nf * sm.ny > 16384 || sm.ny + (long)W * nf * sm.ny > lim)) W /= 2;
+  while (W > 1 && ((long)W * nf * sm.ny > kMaxElems || sm.ny + (long)W * nf * sm.ny > lim)) W /= 2;
+  return W;
+}
+
+hipError_t launch_tf_fields_y(const DevOptics* opt, const Sampling& sm, int npatch, float2* ab,
+                              double* partials, hipStream_t s) {
+  FftPlan plan;
+  if (!make_plan(sm.ny, &plan)) return hipErrorInvalidValue;
+  const int nf = sm.model == kFluor3D ? 1 : 2;
+  const int W = tf_tile_width(sm);
   const long tiles = (sm.nx + W - 1) / W;
   const long nwg = tiles * sm.nz * (long)npatch;
-  const int thr = threads_for_tf((long)sm.ny * nf * W);
+  const int thr = threads_for((long)sm.ny * nf * W);
   const size_t lds = (size_t)(sm.ny + sm.ny * nf * W) * sizeof(float2);
   { ScopedTiming _t("k_tf_fields_y", s);
-  hipLaunchKernelGGL(k_tf_fields_y, dim3((unsigned)nwg), dim3(thr), lds, s, opt, sm, ab, W, tiles,
-                     plan); }
+  hipLaunchKernelGGL(k_tf_fields_y, dim3((unsigned)nwg), dim3(thr), lds, s, opt, sm, ab, partials, W,
+                     tiles, plan); }
   return hipGetLastError();
 }
 
 // ------------------------------------------------------------------ rows: label-free
 
 // out[patch * patch_stride + p * pstride + z * zstride + y * Xh + k], p = 0 phase, 1 absorption
-__global__ __launch_bounds__(1024) void k_tf_rows_lf(const DevOptics* __restrict__ opt,
-                                                     Sampling sm, const float2* __restrict__ ab,
+__device__ __forceinline__ double pupil_total(const double* partials, long tiles_x) {
+  double t = 0.0;
+  for (long i = 0; i < tiles_x; ++i) t += partials[i];
+  return t;
+}
+
+__global__ __launch_bounds__(1024) void k_tf_rows_lf(const double* __restrict__ partials,
+                                                     long tiles_x, Sampling sm,
+                                                     const float2* __restrict__ ab,
                                                      float2* __restrict__ out, long patch_stride,
                                                      long pstride, long zstride, int rows_per_wg,
                                                      long wg_per_patch, FftPlan plan) {
+  __shared__ double ibg_s;
   extern __shared__ float2 smem[];
   const int Y = sm.ny, X = sm.nx, Z = sm.nz, Xh = X / 2 + 1;
   float2* tw = smem;
@@ -185,16 +188,17 @@ __global__ __launch_bounds__(1024) void k_tf_rows_lf(const DevOptics* __restrict
   const int nr = (int)min((long)rows_per_wg, rpp - row0);
   const float2* a_src = ab + (patch * 2 + 0) * rpp * X;
   const float2* b_src = ab + (patch * 2 + 1) * rpp * X;
-  for (int e = tid; e < nr * 2 * X; e += nthr) {
+  if (tid == 0) ibg_s = pupil_total(partials + patch * tiles_x, tiles_x);
+  gather_to_lds(buf, nr * 2 * X, tid, nthr, [&](int e) {
     const int i = e % X;
     const int t = e / X;
     const int f = t & 1, r = t >> 1;
     const float2* src = f ? b_src : a_src;
-    buf[(2 * r + f) * X + i] = src[(row0 + r) * X + i];
-  }
+    return src[(row0 + r) * X + i];
+  });
   __syncthreads();
   lds_fft(buf, LdsLines{2 * nr, 1, X, false}, plan, tw, 1.f, tid, nthr);
-  const float cs = (float)(1.0 / ((double)X * (double)Y * opt[patch].ibg));
+  const float cs = (float)(1.0 / ((double)X * (double)Y * ibg_s));
   for (int e = tid; e < nr * X; e += nthr) {
     const int r = e / X, i = e - r * X;
     const float2 a = buf[2 * r * X + i], b = buf[(2 * r + 1) * X + i];
@@ -216,32 +220,35 @@ __global__ __launch_bounds__(1024) void k_tf_rows_lf(const DevOptics* __restrict
   }
 }
 
-hipError_t launch_tf_rows_labelfree(const DevOptics* opt, const Sampling& sm, int npatch,
+hipError_t launch_tf_rows_labelfree(const double* partials, const Sampling& sm, int npatch,
                                     const float2* ab, float2* out, long patch_stride,
                                     long pstride, long zstride, hipStream_t s) {
+  const long tiles_x = (sm.nx + tf_tile_width(sm) - 1) / tf_tile_width(sm);
   FftPlan plan;
   if (!make_plan(sm.nx, &plan)) return hipErrorInvalidValue;
   int R = 2048 / sm.nx;                       // rows per workgroup (2 lines each)
   if (R < 1) R = 1;
-  while (R > 1 && 2L * R * sm.nx > 16384) --R;
+  while (R > 1 && 2L * R * sm.nx > kMaxElems) --R;
   const long rpp = (long)sm.nz * sm.ny;
   const long wpp = (rpp + R - 1) / R;
   const long nwg = wpp * npatch;
-  const int thr = threads_for_tf(2L * R * sm.nx);
+  const int thr = threads_for(2L * R * sm.nx);
   const size_t lds = (size_t)(sm.nx + 2 * R * sm.nx) * sizeof(float2);
   { ScopedTiming _t("k_tf_rows_lf", s);
-  hipLaunchKernelGGL(k_tf_rows_lf, dim3((unsigned)nwg), dim3(thr), lds, s, opt, sm, ab, out,
-                     patch_stride, pstride, zstride, R, wpp, plan); }
+  hipLaunchKernelGGL(k_tf_rows_lf, dim3((unsigned)nwg), dim3(thr), lds, s, partials, tiles_x, sm, ab,
+                     out, patch_stride, pstride, zstride, R, wpp, plan); }
   return hipGetLastError();
 }
 
 // ------------------------------------------------------------------ rows: fluorescence
 
 // h: [patch][z][y][x] complex (after the inverse Y pass); out: [patch][z][y][Xh]
-__global__ __launch_bounds__(1024) void k_tf_rows_fl(const DevOptics* __restrict__ opt,
-                                                     Sampling sm, const float2* __restrict__ h,
+__global__ __launch_bounds__(1024) void k_tf_rows_fl(const double* __restrict__ partials,
+                                                     long tiles_x, Sampling sm,
+                                                     const float2* __restrict__ h,
                                                      float2* __restrict__ out, int pairs_per_wg,
                                                      long wg_per_patch, FftPlan plan) {
+  __shared__ double ibg_s;
   extern __shared__ float2 smem[];
   const int Y = sm.ny, X = sm.nx, Z = sm.nz, Xh = X / 2 + 1;
   float2* tw = smem;
@@ -254,13 +261,14 @@ __global__ __launch_bounds__(1024) void k_tf_rows_fl(const DevOptics* __restrict
   const int nrows = (int)min(2L * pairs_per_wg, rpp - row0);
   const int np = (nrows + 1) / 2;
   const float2* src = h + patch * rpp * X;
-  for (int e = tid; e < 2 * np * X; e += nthr) {
+  if (tid == 0) ibg_s = pupil_total(partials + patch * tiles_x, tiles_x);
+  gather_to_lds(buf, 2 * np * X, tid, nthr, [&](int e) {
     const int l = e / X, i = e - l * X;
-    buf[e] = l < nrows ? src[(row0 + l) * X + i] : make_float2(0.f, 0.f);
-  }
+    return l < nrows ? src[(row0 + l) * X + i] : make_float2(0.f, 0.f);
+  });
   __syncthreads();
   lds_fft(buf, LdsLines{2 * np, 1, X, false}, plan, tw, 1.f, tid, nthr);
-  const double norm = 1.0 / ((double)Z * (double)X * (double)Y * opt[patch].ibg);
+  const double norm = 1.0 / ((double)Z * (double)X * (double)Y * ibg_s);
   const float nm = (float)norm;
   for (int e = tid; e < np * X; e += nthr) {
     const int q = e / X, i = e - q * X;
@@ -281,21 +289,22 @@ __global__ __launch_bounds__(1024) void k_tf_rows_fl(const DevOptics* __restrict
   }
 }
 
-hipError_t launch_tf_rows_fluor(const DevOptics* opt, const Sampling& sm, int npatch,
+hipError_t launch_tf_rows_fluor(const double* partials, const Sampling& sm, int npatch,
                                 const float2* h, float2* out, hipStream_t s) {
+  const long tiles_x = (sm.nx + tf_tile_width(sm) - 1) / tf_tile_width(sm);
   FftPlan plan;
   if (!make_plan(sm.nx, &plan)) return hipErrorInvalidValue;
   int Q = 2048 / sm.nx;                       // row pairs per workgroup
   if (Q < 1) Q = 1;
-  while (Q > 1 && 2L * Q * sm.nx > 16384) --Q;
+  while (Q > 1 && 2L * Q * sm.nx > kMaxElems) --Q;
   const long rpp = (long)sm.nz * sm.ny;
   const long wpp = (rpp + 2 * Q - 1) / (2 * Q);
   const long nwg = wpp * npatch;
-  const int thr = threads_for_tf(2L * Q * sm.nx);
+  const int thr = threads_for(2L * Q * sm.nx);
   const size_t lds = (size_t)(sm.nx + 2 * Q * sm.nx) * sizeof(float2);
   { ScopedTiming _t("k_tf_rows_fl", s);
-  hipLaunchKernelGGL(k_tf_rows_fl, dim3((unsigned)nwg), dim3(thr), lds, s, opt, sm, h, out, Q,
-                     wpp, plan); }
+  hipLaunchKernelGGL(k_tf_rows_fl, dim3((unsigned)nwg), dim3(thr), lds, s, partials, tiles_x, sm, h,
+                     out, Q, wpp, plan); }
   return hipGetLastError();
 }
 
@@ -317,11 +326,26 @@ __global__ __launch_bounds__(1024) void k_tf_pol5_z(const DevOptics* __restrict_
   const long m0 = tile * W;
   const int weff = (int)min((long)W, M - m0);
   const float2* src = uw + patch * 2L * Z * M;
-  for (int e = tid; e < 2 * Z * W; e += nthr) {
-    const int w = e % W;
-    const int t = e / W;
-    const int z = t % Z, f = t / Z;
-    buf[(z * 2 + f) * W + w] = w < weff ? src[((long)f * Z + z) * M + m0 + w] : make_float2(0.f, 0.f);
+  {
+    float2 t[kEmax];
+#pragma unroll
+    for (int i = 0; i < kEmax; ++i) {
+      const int e = tid + i * nthr;
+      if (e < 2 * Z * W) {
+        const int w = e % W, r = e / W;
+        const int z = r % Z, f = r / Z;
+        t[i] = w < weff ? src[((long)f * Z + z) * M + m0 + w] : make_float2(0.f, 0.f);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < kEmax; ++i) {
+      const int e = tid + i * nthr;
+      if (e < 2 * Z * W) {
+        const int w = e % W, r = e / W;
+        const int z = r % Z, f = r / Z;
+        buf[(z * 2 + f) * W + w] = t[i];
+      }
+    }
   }
   __syncthreads();
   lds_fft(buf, LdsLines{2 * W, 2 * W, 1, true}, plan, tw, -1.f, tid, nthr);
@@ -351,10 +375,10 @@ hipError_t launch_tf_pol5_z(const DevOptics* opt, const Sampling& sm, int npatch
   const long M = (long)sm.ny * (sm.nx / 2 + 1);
   const long lim = lds_limit_bytes() / (long)sizeof(float2);
   int W = 16;
-  while (W > 1 && (2L * W * sm.nz > 16384 || sm.nz + 2L * W * sm.nz > lim)) W /= 2;
+  while (W > 1 && (2L * W * sm.nz > kMaxElems || sm.nz + 2L * W * sm.nz > lim)) W /= 2;
   const long tiles = (M + W - 1) / W;
   const long nwg = tiles * npatch;
-  const int thr = threads_for_tf(2L * sm.nz * W);
+  const int thr = threads_for(2L * sm.nz * W);
   const size_t lds = (size_t)(sm.nz + 2 * sm.nz * W) * sizeof(float2);
   { ScopedTiming _t("k_tf_pol5_z", s);
   hipLaunchKernelGGL(k_tf_pol5_z, dim3((unsigned)nwg), dim3(thr), lds, s, opt, sm.nz, M, uw, tf, W,
