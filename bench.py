@@ -96,6 +96,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-nz", type=int, default=96)
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--tune-patches", type=int, default=256)
+    ap.add_argument("--tune-iters", type=int, default=100)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for HBM counters)")
     args = ap.parse_args()
@@ -211,6 +214,8 @@ def main():
         "kernels": kernels,
     }
 
+    if not args.no_autotune:
+        out["autotune"] = autotune_section(api, torch, dev, args.tune_patches, args.tune_iters)
     if args.calibrate_copy:
         src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
@@ -221,6 +226,72 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(o, args.cpu_sample_nz)
     print(json.dumps(out))
+
+
+# Auto-tune workload: 256 patches of 32x128x128 (dz 0.2, dx 0.1 um), lambda0 0.532,
+# NA_ill 0.5, n 1.33, soft pupil edges; per-patch truth defocus ~U(-2, 2) um,
+# NA_det ~U(1.0, 1.3), illumination zenith tilt ~U(0, 30 deg).
+TUNE = dict(model=2, nz=32, ny=128, nx=128, dz=0.2, dy=0.1, dx=0.1, wavelength=0.532, na_ill=0.5,
+            na_det=1.15, n_medium=1.33, defocus=0.0, tilt_zenith=0.0, tilt_azimuth=0.0,
+            edge_width=0.5, swing=0.1)
+TUNE_RANGE = np.array([4.0, 0.3, math.radians(30.0)])
+TUNE_LR = (0.02, 0.005, 0.005, 0.001)
+TUNE_LO = (-2.5, 1.0, 0.0, -1.0)
+TUNE_HI = (2.5, 1.3, math.radians(32.0), 1.0)
+
+
+def autotune_section(api, torch, dev, n, iters):
+    """Patches/s of the batched GPU auto-tune (single start and 8-start multistart)
+    and the median normalised parameter error |theta - truth| / range."""
+    import synth
+    rng = np.random.default_rng(4001)
+    truth = np.stack([rng.uniform(-2, 2, n), rng.uniform(1.0, 1.3, n),
+                      rng.uniform(0.0, math.radians(30.0), n)], 1)
+    opts_true = [api.Optics(**dict(TUNE, defocus=t[0], na_det=t[1], tilt_zenith=t[2])) for t in truth]
+    objs = np.stack([synth.thin_cells((TUNE["ny"], TUNE["nx"]), TUNE["dx"], 20, seed=5000 + i)
+                     for i in range(n)])
+    tf_true = api.transfer_function(opts_true, device=dev)
+    clean = api.forward(opts_true, tf_true, torch.from_numpy(objs).to(dev))
+    d = torch.from_numpy(synth.poisson_gaussian(clean.cpu().numpy(), seed=4002)).to(dev)
+    del tf_true, clean
+    nominal = api.Optics(**TUNE)
+    tf_nom = api.transfer_function([nominal], device=dev)
+    eta = 1e-2 * float((tf_nom.abs() ** 2).sum(dim=2).max())
+    nu_c = (TUNE["na_det"] + TUNE["na_ill"]) / TUNE["wavelength"]
+    starts = [api.Optics(**dict(TUNE, tilt_zenith=math.radians(15.0))) for _ in range(n)]
+
+    def err(th):
+        e = np.abs(th[:, :3] - truth) / TUNE_RANGE
+        return float(np.median(e.max(axis=1))), [float(x) for x in np.median(e, axis=0)]
+
+    res = {"workload": f"{n} patches 32x128x128, {iters} Adam iterations, hipGraph replay"}
+    for label, M in (("single_start", 1), ("multistart_8", 8)):
+        theta0 = None
+        if M > 1:
+            grid = np.stack(np.meshgrid([-1.5, -0.5, 0.5, 1.5], [math.radians(7.5), math.radians(22.5)],
+                                        indexing="ij"), -1).reshape(-1, 2)
+            theta0 = np.zeros((n, M, 4))
+            theta0[:, :, 0] = grid[None, :, 0]
+            theta0[:, :, 1] = TUNE["na_det"]
+            theta0[:, :, 2] = grid[None, :, 1]
+        ws = torch.empty(api.tune_workspace_size(starts, M), dtype=torch.uint8, device=dev)
+        api.autotune(starts[:1], d[:1], eta, iters=2, lr=TUNE_LR, lo=TUNE_LO, hi=TUNE_HI, multistart=M,
+                     theta0=None if theta0 is None else theta0[:1], nu_c=nu_c, use_graph=True, ws=ws)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out, loss, _, _ = api.autotune(starts, d, eta, iters=iters, lr=TUNE_LR, lo=TUNE_LO, hi=TUNE_HI,
+                                       multistart=M, theta0=theta0, nu_c=nu_c, use_graph=True, ws=ws)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        th = np.array([[o.defocus, o.na_det, o.tilt_zenith, o.tilt_azimuth] for o in out])
+        med, per = err(th)
+        res[label] = {"patches_per_s": n / dt, "seconds": round(dt, 3), "starts": M,
+                      "median_norm_param_err": round(med, 4),
+                      "median_norm_err_defocus_na_tilt": [round(x, 4) for x in per]}
+        del ws
+        print(f"[bench] autotune {label}: {n / dt:.1f} patches/s, median err {med:.3f}",
+              file=sys.stderr, flush=True)
+    return res
 
 
 def cpu_baseline(o, nz):

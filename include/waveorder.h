@@ -136,6 +136,54 @@ int wo_reconstruct(const wo_optics* o, int32_t n, const void* tf, const float* d
 int wo_adjoint(const wo_optics* o, int32_t n, const void* tf, const float* r, float* g_out,
                void* ws, size_t ws_bytes, void* stream);
 
+/* ---------------------------------------------------------------- auto-tune
+ * Thin phase-from-defocus model only (WO_MODEL_LABELFREE_THIN).  Parameters
+ * theta = (defocus, na_det, tilt_zenith, tilt_azimuth) are tuned per patch to
+ * maximise the power of the reconstructed phase in a mid-band of lateral
+ * frequencies (Results, "Physics-guided ML auto-tunes multi-contrast blind
+ * deconvolution"; Methods, "Cell-scale optical pooled screen data";
+ * Ext. Data Fig. 3).  The band is nu_c/8 <= |nu| <= nu_c/4 with nu_c the
+ * transverse cutoff, by default (na_det + na_ill)/wavelength of the patch's
+ * given optics, held fixed while theta moves; the loss is
+ * L = -(1/|band|) sum_band |F_phase(nu)|^2 on the unnormalised 2D DFT of the
+ * Tikhonov phase reconstruction.  Gradients are hand-written reverse mode
+ * through the solve and the transfer-function synthesis; the transfer
+ * function is recomputed every iteration.  Soft pupil edges (edge_width > 0)
+ * are needed for non-zero NA and tilt gradients. */
+
+/* Workspace bytes for wo_midband_loss_grad (starts = 1) or wo_autotune. */
+size_t wo_tune_workspace_size(const wo_optics* o, int32_t n, int32_t starts);
+
+/* Loss and dL/dtheta at each patch's optics.  d: device [n][nz][ny][nx]
+ * stacks; eta, nu_c: host [n] (nu_c may be NULL or <= 0 for the default);
+ * loss_out: host [n]; grad_out: host [n][4] or NULL.  Synchronises `stream`
+ * before returning. */
+int wo_midband_loss_grad(const wo_optics* o, int32_t n, const float* d, const double* eta,
+                         const double* nu_c, double* loss_out, double* grad_out, void* ws,
+                         size_t ws_bytes, void* stream);
+
+typedef struct wo_autotune_opts {
+  int32_t iters;           /* Adam iterations (the paper uses 100) */
+  int32_t multistart;      /* starts per patch, M >= 1; the lowest final loss wins */
+  int32_t use_graph;       /* capture one iteration in a HIP graph and replay it */
+  int32_t tune_mask;       /* bit j set: theta_j is tuned */
+  double lr[4];            /* Adam learning rates per parameter */
+  double lo[4], hi[4];     /* box for theta (NA is further capped inside the shell) */
+  const double* theta0;    /* host [n][M][4] starting theta, or NULL: each patch's optics */
+  const double* nu_c;      /* host [n] band cutoffs, or NULL for the default */
+  double* all_theta_out;   /* host [n][M][4] final theta of every start, or NULL */
+  double* all_loss_out;    /* host [n][M] final loss of every start, or NULL */
+} wo_autotune_opts;
+
+/* Adam (beta 0.9, 0.999, eps 1e-8) on theta for opts->iters iterations, every
+ * patch and start in one batched launch sequence; theta is clipped to the box
+ * after each step.  On return o[i] holds the best start's theta and
+ * loss_out[i] (host, may be NULL) its loss at that theta.  d: device
+ * [n][nz][ny][nx]; eta: host [n].  Synchronises `stream` before returning. */
+int wo_autotune(wo_optics* o, int32_t n, const float* d, const double* eta,
+                const wo_autotune_opts* opts, double* loss_out, void* ws, size_t ws_bytes,
+                void* stream);
+
 /* Instrumentation (not part of the method): while enabled, every kernel the
  * library launches is bracketed by HIP events on the stream it runs on.
  * wo_timing_report() waits for the recorded events, writes one line

@@ -31,7 +31,7 @@ OP_ADJOINT = 3
 
 SYMBOLS = ("wo_bank_shape", "wo_workspace_size", "wo_transfer_function", "wo_forward",
            "wo_reconstruct", "wo_adjoint", "wo_strerror", "wo_version", "wo_timing_enable",
-           "wo_timing_report")
+           "wo_timing_report", "wo_tune_workspace_size", "wo_midband_loss_grad", "wo_autotune")
 
 _FIELDS = ("model", "nz", "ny", "nx", "dz", "dy", "dx", "wavelength", "na_ill", "na_det",
            "n_medium", "defocus", "tilt_zenith", "tilt_azimuth", "edge_width", "swing")
@@ -62,6 +62,15 @@ class Optics:
     tilt_azimuth: float = 0.0
     edge_width: float = 0.0
     swing: float = 0.1
+
+
+class WoAutotuneOpts(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("multistart", ctypes.c_int32),
+                ("use_graph", ctypes.c_int32), ("tune_mask", ctypes.c_int32),
+                ("lr", ctypes.c_double * 4), ("lo", ctypes.c_double * 4), ("hi", ctypes.c_double * 4),
+                ("theta0", ctypes.POINTER(ctypes.c_double)), ("nu_c", ctypes.POINTER(ctypes.c_double)),
+                ("all_theta_out", ctypes.POINTER(ctypes.c_double)),
+                ("all_loss_out", ctypes.POINTER(ctypes.c_double))]
 
 
 class WoError(RuntimeError):
@@ -95,6 +104,11 @@ def load(path: str = LIB_PATH):
     lib.wo_strerror.argtypes = [ctypes.c_int]
     lib.wo_strerror.restype = ctypes.c_char_p
     lib.wo_version.restype = ctypes.c_int
+    dp = ctypes.POINTER(ctypes.c_double)
+    lib.wo_tune_workspace_size.argtypes = [op, i32, i32]
+    lib.wo_tune_workspace_size.restype = sz
+    lib.wo_midband_loss_grad.argtypes = [op, i32, vp, dp, dp, dp, dp, vp, sz, vp]
+    lib.wo_autotune.argtypes = [op, i32, vp, dp, ctypes.POINTER(WoAutotuneOpts), dp, vp, sz, vp]
     lib.wo_timing_enable.argtypes = [ctypes.c_int]
     lib.wo_timing_report.argtypes = [ctypes.c_char_p, ctypes.c_size_t]
     for name in SYMBOLS:
@@ -243,3 +257,144 @@ def timing_report() -> dict:
         name, cnt, ms = line.split()
         out[name] = (int(cnt), float(ms))
     return out
+
+
+# ---------------------------------------------------------------- auto-tune (thin model)
+
+PARAMS = ("defocus", "na_det", "tilt_zenith", "tilt_azimuth")
+PAPER_LR = (0.02, 0.005, 0.005, 0.001)   # um, NA (proposed), rad, rad
+
+
+def _dbl(values):
+    import numpy as np
+    a = np.ascontiguousarray(np.asarray(values, dtype=np.float64))
+    return a, a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def tune_workspace_size(optics, starts: int = 1) -> int:
+    arr = optics_array(optics)
+    return int(load().wo_tune_workspace_size(arr, len(arr), starts))
+
+
+def midband_loss_grad(optics, d, eta, nu_c=None, ws=None, stream=None):
+    """Mid-band loss and dL/dtheta per patch (numpy arrays (n,), (n, 4))."""
+    import numpy as np
+    import torch
+    lib = load()
+    arr = optics_array(optics)
+    n = len(arr)
+    d = d.contiguous()
+    need = tune_workspace_size(optics, 1)
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(need, dtype=torch.uint8, device=d.device)
+    eta_a, eta_p = _dbl(np.broadcast_to(eta, (n,)))
+    nu_a, nu_p = _dbl(np.zeros(n) if nu_c is None else np.broadcast_to(nu_c, (n,)))
+    loss = np.zeros(n)
+    grad = np.zeros((n, 4))
+    _check(lib.wo_midband_loss_grad(arr, n, _ptr(d), eta_p, nu_p,
+                                    loss.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                    grad.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                    _ptr(ws), ws.numel(), _stream(stream)), "wo_midband_loss_grad")
+    return loss, grad
+
+
+def autotune(optics, d, eta, iters=100, lr=PAPER_LR, lo=(-1e300,) * 4, hi=(1e300,) * 4,
+             mask=0b0111, multistart=1, theta0=None, nu_c=None, use_graph=False, ws=None,
+             stream=None):
+    """Adam auto-tune of theta for every patch; returns (optics list, loss, all_theta, all_loss)."""
+    import copy
+    import numpy as np
+    import torch
+    lib = load()
+    optics = list(optics) if isinstance(optics, (list, tuple)) else [optics]
+    arr = optics_array(optics)
+    n = len(arr)
+    M = int(multistart)
+    d = d.contiguous()
+    need = tune_workspace_size(optics, M)
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(need, dtype=torch.uint8, device=d.device)
+    opts = WoAutotuneOpts()
+    opts.iters, opts.multistart, opts.use_graph, opts.tune_mask = int(iters), M, int(bool(use_graph)), int(mask)
+    for j in range(4):
+        opts.lr[j], opts.lo[j], opts.hi[j] = float(lr[j]), float(lo[j]), float(hi[j])
+    keep = []
+    if theta0 is not None:
+        a, p = _dbl(np.reshape(theta0, (n * M * 4,)))
+        keep.append(a)
+        opts.theta0 = p
+    if nu_c is not None:
+        a, p = _dbl(np.broadcast_to(nu_c, (n,)))
+        keep.append(a)
+        opts.nu_c = p
+    all_theta = np.zeros((n, M, 4))
+    all_loss = np.zeros((n, M))
+    opts.all_theta_out = all_theta.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    opts.all_loss_out = all_loss.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    eta_a, eta_p = _dbl(np.broadcast_to(eta, (n,)))
+    loss = np.zeros(n)
+    _check(lib.wo_autotune(arr, n, _ptr(d), eta_p, ctypes.byref(opts),
+                           loss.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), _ptr(ws), ws.numel(),
+                           _stream(stream)), "wo_autotune")
+    out = []
+    for i, o in enumerate(optics):
+        oo = copy.copy(o)
+        for f in PARAMS:
+            if isinstance(oo, dict):
+                oo[f] = getattr(arr[i], f)
+            else:
+                setattr(oo, f, getattr(arr[i], f))
+        out.append(oo)
+    return out, loss, all_theta, all_loss
+
+
+# ---------------------------------------------------------------- autograd wrappers
+
+def _autograd():
+    import torch
+
+    class LinearForward(torch.autograd.Function):
+        """d = H f + b with the adjoint kernel as backward: grad_f = H^H grad_d."""
+
+        @staticmethod
+        def forward(ctx, f, optics, tf, b):
+            ctx.optics, ctx.tf = optics, tf
+            return forward(optics, tf, f, b=b)
+
+        @staticmethod
+        def backward(ctx, g):
+            return adjoint(ctx.optics, ctx.tf, g.contiguous()), None, None, None
+
+    class MidbandLoss(torch.autograd.Function):
+        """Mid-band loss of each patch as a function of theta (n, 4) (float64, host);
+        backward uses the hand-written transfer-function gradient."""
+
+        @staticmethod
+        def forward(ctx, theta, optics, d, eta, nu_c):
+            import copy
+            opts = []
+            for i, o in enumerate(optics):
+                oo = copy.copy(o)
+                for j, f in enumerate(PARAMS):
+                    setattr(oo, f, float(theta[i, j]))
+                opts.append(oo)
+            loss, grad = midband_loss_grad(opts, d, eta, nu_c)
+            ctx.save_for_backward(torch.from_numpy(grad))
+            return torch.from_numpy(loss)
+
+        @staticmethod
+        def backward(ctx, gout):
+            (grad,) = ctx.saved_tensors
+            return gout[:, None] * grad, None, None, None, None
+
+    return LinearForward, MidbandLoss
+
+
+def linear_forward_fn(f, optics, tf, b=None):
+    """Differentiable forward model (backward = wo_adjoint)."""
+    return _autograd()[0].apply(f, optics, tf, b)
+
+
+def midband_loss_fn(theta, optics, d, eta, nu_c=None):
+    """Differentiable mid-band loss in theta (backward = hand-written TF gradient)."""
+    return _autograd()[1].apply(theta, optics, d, eta, nu_c)

@@ -276,6 +276,173 @@ int run_linear(const wo_optics* o, int32_t n, const Shape& s, const float2* tf, 
   return WO_OK;
 }
 
+
+// ---------------------------------------------------------------- auto-tune
+
+struct TuneLayout {
+  int nv;
+  long tiles, lbpp, dwpp;
+  size_t off_opt, off_st, off_D, off_bank, off_ab, off_gam, off_pp, off_lp, off_dp, off_gp, off_ip,
+      total;
+};
+
+TuneLayout tune_layout(const wo_optics* o, int32_t n, int32_t starts) {
+  TuneLayout L;
+  const Sampling sm = sampling_of(o);
+  const long Z = o->nz, Y = o->ny, X = o->nx, Xh = X / 2 + 1;
+  L.nv = n * starts;
+  const int W = tf_tile_width(sm);
+  L.tiles = (X + W - 1) / W;
+  L.lbpp = loss_blocks(sm);
+  L.dwpp = bwd_wg_per_patch(sm);
+  size_t b = 0;
+  auto take = [&](size_t bytes) { size_t o0 = b; b += align_up(bytes); return o0; };
+  L.off_opt = take((size_t)L.nv * sizeof(DevOptics));
+  L.off_st = take((size_t)L.nv * sizeof(TuneState));
+  L.off_D = take((size_t)n * Z * Y * Xh * sizeof(float2));
+  L.off_bank = take((size_t)L.nv * 2 * Z * Y * Xh * sizeof(float2));
+  L.off_ab = take((size_t)L.nv * 2 * Z * Y * X * sizeof(float2));
+  L.off_gam = take((size_t)L.nv * 2 * Z * Y * X * sizeof(float));
+  L.off_pp = take((size_t)L.nv * L.tiles * sizeof(double));
+  L.off_lp = take((size_t)L.nv * L.lbpp * sizeof(double));
+  L.off_dp = take((size_t)L.nv * L.dwpp * sizeof(double));
+  L.off_gp = take((size_t)L.nv * Z * L.tiles * 4 * sizeof(double));
+  L.off_ip = take((size_t)L.nv * L.tiles * 4 * sizeof(double));
+  L.total = b;
+  return L;
+}
+
+// Number of lateral frequencies (full spectrum) with nu_c/8 <= |nu| <= nu_c/4.
+double band_count(const wo_optics* o, double nu_c) {
+  long cnt = 0;
+  const double vy = 1.0 / ((double)o->ny * o->dy), vx = 1.0 / ((double)o->nx * o->dx);
+  for (int ky = 0; ky < o->ny; ++ky) {
+    const int sy = ky < (o->ny + 1) / 2 ? ky : ky - o->ny;
+    const double fy = sy * vy;
+    for (int kx = 0; kx < o->nx; ++kx) {
+      const int sx = kx < (o->nx + 1) / 2 ? kx : kx - o->nx;
+      const double fx = sx * vx;
+      const double r = sqrt(fy * fy + fx * fx);
+      if (r >= nu_c / 8.0 && r <= nu_c / 4.0) ++cnt;
+    }
+  }
+  return (double)cnt;
+}
+
+DevOptics dev_optics(const wo_optics& o) {
+  DevOptics d;
+  memset(&d, 0, sizeof(d));
+  d.wavelength = o.wavelength;
+  d.na_ill = o.na_ill;
+  d.na_det = o.na_det;
+  d.n_medium = o.n_medium;
+  d.defocus = o.defocus;
+  d.tilt_zenith = o.tilt_zenith;
+  d.tilt_azimuth = o.tilt_azimuth;
+  d.edge_width = o.edge_width;
+  return d;
+}
+
+// One auto-tune iteration for all virtual patches (update = 0: loss and
+// gradient only).
+int tune_iteration(const wo_optics* o, const TuneLayout& L, char* w, int starts, int update,
+                   hipStream_t hs) {
+  const Sampling sm = sampling_of(o);
+  const long Z = o->nz, Y = o->ny, Xh = o->nx / 2 + 1;
+  const long plane = Y * Xh;
+  DevOptics* dopt = (DevOptics*)(w + L.off_opt);
+  TuneState* st = (TuneState*)(w + L.off_st);
+  float2* D = (float2*)(w + L.off_D);
+  float2* bank = (float2*)(w + L.off_bank);
+  float2* ab = (float2*)(w + L.off_ab);
+  float* gam = (float*)(w + L.off_gam);
+  double* pp = (double*)(w + L.off_pp);
+  double* lp = (double*)(w + L.off_lp);
+  double* dp = (double*)(w + L.off_dp);
+  double* gp = (double*)(w + L.off_gp);
+  double* ip = (double*)(w + L.off_ip);
+  const int nv = L.nv;
+  WO_TRY(launch_tf_fields_y(dopt, sm, nv, ab, pp, hs));
+  WO_TRY(launch_tf_rows_labelfree(pp, sm, nv, ab, bank, 2 * Z * plane, plane, 2 * plane, hs));
+  WO_TRY(launch_cols(bank, (int)Y, Xh, 2 * Z, 2 * Z, nv, -1.f, hs, "k_cols_y_tf"));
+  WO_TRY(launch_loss_grad(dopt, st, sm, nv, D, bank, lp, starts, hs));
+  WO_TRY(launch_cols(bank, (int)Y, Xh, 2 * Z, 2 * Z, nv, 1.f, hs, "k_cols_y_grad"));
+  RowGroups g{2 * Z * Y, 2 * Z * Y, 2 * Z * Y, nv};
+  WO_TRY(launch_rows_c2r(bank, gam, o->nx, g, 1.f, hs));
+  WO_TRY(launch_tf_rows_bwd(pp, sm, nv, ab, gam, dp, hs));
+  WO_TRY(launch_tf_grad_y(dopt, sm, nv, ab, gp, ip, hs));
+  WO_TRY(launch_adam(dopt, st, sm, nv, pp, lp, dp, gp, ip, update, hs));
+  return WO_OK;
+}
+
+int validate_thin(const wo_optics* o, int32_t n) {
+  int st = validate(o, n);
+  if (st) return st;
+  if (o->model != WO_MODEL_LABELFREE_THIN) return WO_EUNSUPPORTED;
+  return WO_OK;
+}
+
+// Set-up shared by the loss/gradient call and the auto-tune: per-virtual-patch
+// optics and tune state, and the 2D spectra of the data stacks.
+int tune_setup(const wo_optics* o, int32_t n, int starts, const double* theta0, const float* d,
+               const double* eta, const double* nu_c, const double* lr, const double* lo,
+               const double* hi, int mask, const TuneLayout& L, char* w, hipStream_t hs) {
+  const int nv = L.nv;
+  std::vector<DevOptics> hopt(nv);
+  std::vector<TuneState> hst(nv);
+  for (int v = 0; v < nv; ++v) {
+    const int i = v / starts;
+    hopt[v] = dev_optics(o[i]);
+    if (theta0) {
+      hopt[v].defocus = theta0[4 * v + 0];
+      hopt[v].na_det = theta0[4 * v + 1];
+      hopt[v].tilt_zenith = theta0[4 * v + 2];
+      hopt[v].tilt_azimuth = theta0[4 * v + 3];
+    }
+    TuneState& t = hst[v];
+    memset(&t, 0, sizeof(t));
+    for (int j = 0; j < 4; ++j) {
+      t.lr[j] = lr ? lr[j] : 0.0;
+      t.lo[j] = lo ? lo[j] : -1e300;
+      t.hi[j] = hi ? hi[j] : 1e300;
+    }
+    t.eta = eta[i];
+    t.nu_c = (nu_c && nu_c[i] > 0) ? nu_c[i] : (o[i].na_det + o[i].na_ill) / o[i].wavelength;
+    t.band_count = band_count(&o[i], t.nu_c);
+    if (t.band_count < 1) return WO_EINVAL;
+    t.mask = mask;
+  }
+  // every virtual patch must describe valid optics at its start
+  for (int v = 0; v < nv; ++v) {
+    wo_optics ov = o[v / starts];
+    ov.defocus = hopt[v].defocus;
+    ov.na_det = hopt[v].na_det;
+    ov.tilt_zenith = hopt[v].tilt_zenith;
+    ov.tilt_azimuth = hopt[v].tilt_azimuth;
+    int stt = check_optics(&ov);
+    if (stt) return stt;
+  }
+  WO_TRY(launch_set_params((DevOptics*)(w + L.off_opt), hopt.data(), nv, hs));
+  WO_TRY(launch_set_tune((TuneState*)(w + L.off_st), hst.data(), nv, hs));
+  const long Z = o->nz, Y = o->ny;
+  float2* D = (float2*)(w + L.off_D);
+  RowGroups g{Z * Y, Z * Y, Z * Y, n};
+  WO_TRY(launch_rows_r2c(d, D, o->nx, g, hs));
+  WO_TRY(launch_cols(D, (int)Y, o->nx / 2 + 1, Z, Z, n, -1.f, hs, "k_cols_y_data"));
+  return WO_OK;
+}
+
+// Largest theta box that keeps every pupil strictly inside the shell and the
+// support inside the lateral band, intersected with the caller's box.
+void clamp_box(const wo_optics* o, double lo[4], double hi[4]) {
+  const double km = o->n_medium / o->wavelength;
+  const double dnu = fmin(1.0 / (o->nx * o->dx), 1.0 / (o->ny * o->dy));
+  const double hw = o->edge_width * dnu;
+  const double na_max = (km - hw) * o->wavelength * (1.0 - 1e-9);
+  if (hi[1] > na_max) hi[1] = na_max;
+  if (lo[1] < 0.0) lo[1] = 0.0;
+}
+
 }  // namespace
 
 extern "C" {
@@ -468,6 +635,132 @@ int wo_adjoint(const wo_optics* o, int32_t n, const void* tf, const float* r, fl
   if (ws_bytes < linear_ws(n, s)) return WO_ENOMEM;
   return run_linear(o, n, s, (const float2*)tf, r, g_out, nullptr, kModeAdjoint, 0.f, ws,
                     (hipStream_t)stream);
+}
+
+}  // extern "C"
+
+extern "C" {
+
+size_t wo_tune_workspace_size(const wo_optics* o, int32_t n, int32_t starts) {
+  if (!o || n < 1 || starts < 1) return 0;
+  if (o->model != WO_MODEL_LABELFREE_THIN) return 0;
+  return tune_layout(o, n, starts).total;
+}
+
+int wo_midband_loss_grad(const wo_optics* o, int32_t n, const float* d, const double* eta,
+                         const double* nu_c, double* loss_out, double* grad_out, void* ws,
+                         size_t ws_bytes, void* stream) {
+  int st = validate_thin(o, n);
+  if (st) return st;
+  if (!d || !eta || !ws || !loss_out) return WO_EINVAL;
+  for (int i = 0; i < n; ++i)
+    if (!(eta[i] > 0.0)) return WO_EINVAL;
+  const TuneLayout L = tune_layout(o, n, 1);
+  if (ws_bytes < L.total) return WO_ENOMEM;
+  hipStream_t hs = (hipStream_t)stream;
+  char* w = (char*)ws;
+  st = tune_setup(o, n, 1, nullptr, d, eta, nu_c, nullptr, nullptr, nullptr, 0, L, w, hs);
+  if (st) return st;
+  st = tune_iteration(o, L, w, 1, 0, hs);
+  if (st) return st;
+  std::vector<TuneState> h(n);
+  WO_TRY(hipMemcpyAsync(h.data(), w + L.off_st, n * sizeof(TuneState), hipMemcpyDeviceToHost, hs));
+  WO_TRY(hipStreamSynchronize(hs));
+  for (int i = 0; i < n; ++i) {
+    loss_out[i] = h[i].loss;
+    if (grad_out)
+      for (int j = 0; j < 4; ++j) grad_out[4 * i + j] = h[i].grad[j];
+  }
+  return WO_OK;
+}
+
+int wo_autotune(wo_optics* o, int32_t n, const float* d, const double* eta,
+                const wo_autotune_opts* opts, double* loss_out, void* ws, size_t ws_bytes,
+                void* stream) {
+  int st = validate_thin(o, n);
+  if (st) return st;
+  if (!d || !eta || !opts || !ws) return WO_EINVAL;
+  const int starts = opts->multistart < 1 ? 1 : opts->multistart;
+  if (opts->iters < 0) return WO_EINVAL;
+  for (int i = 0; i < n; ++i)
+    if (!(eta[i] > 0.0)) return WO_EINVAL;
+  const TuneLayout L = tune_layout(o, n, starts);
+  if (ws_bytes < L.total) return WO_ENOMEM;
+  double lo[4], hi[4];
+  for (int j = 0; j < 4; ++j) {
+    lo[j] = opts->lo[j];
+    hi[j] = opts->hi[j];
+  }
+  clamp_box(o, lo, hi);
+  hipStream_t hs = (hipStream_t)stream;
+  char* w = (char*)ws;
+  st = tune_setup(o, n, starts, opts->theta0, d, eta, opts->nu_c, opts->lr, lo, hi,
+                  opts->tune_mask, L, w, hs);
+  if (st) return st;
+  if (opts->use_graph && opts->iters > 0) {
+    // capture one iteration on a library stream and replay it
+    static hipStream_t cap = nullptr;
+    if (!cap) WO_TRY(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+    hipEvent_t ev0, ev1;
+    WO_TRY(hipEventCreateWithFlags(&ev0, hipEventDisableTiming));
+    WO_TRY(hipEventCreateWithFlags(&ev1, hipEventDisableTiming));
+    WO_TRY(hipEventRecord(ev0, hs));
+    WO_TRY(hipStreamWaitEvent(cap, ev0, 0));
+    const bool was_timing = timing_enabled();
+    if (was_timing) wo_timing_enable(0);
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    WO_TRY(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+    const int ist = tune_iteration(o, L, w, starts, 1, cap);
+    hipError_t ce = hipStreamEndCapture(cap, &graph);
+    if (was_timing) wo_timing_enable(1);
+    if (ist) return ist;
+    WO_TRY(ce);
+    WO_TRY(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+    for (int it = 0; it < opts->iters; ++it) WO_TRY(hipGraphLaunch(exec, cap));
+    WO_TRY(hipEventRecord(ev1, cap));
+    WO_TRY(hipStreamWaitEvent(hs, ev1, 0));
+    WO_TRY(hipStreamSynchronize(cap));
+    hipGraphExecDestroy(exec);
+    hipGraphDestroy(graph);
+    hipEventDestroy(ev0);
+    hipEventDestroy(ev1);
+  } else {
+    for (int it = 0; it < opts->iters; ++it) {
+      st = tune_iteration(o, L, w, starts, 1, hs);
+      if (st) return st;
+    }
+  }
+  // loss at the final parameters
+  st = tune_iteration(o, L, w, starts, 0, hs);
+  if (st) return st;
+  std::vector<TuneState> h(L.nv);
+  std::vector<DevOptics> ho(L.nv);
+  WO_TRY(hipMemcpyAsync(h.data(), w + L.off_st, L.nv * sizeof(TuneState), hipMemcpyDeviceToHost, hs));
+  WO_TRY(hipMemcpyAsync(ho.data(), w + L.off_opt, L.nv * sizeof(DevOptics), hipMemcpyDeviceToHost, hs));
+  WO_TRY(hipStreamSynchronize(hs));
+  for (int i = 0; i < n; ++i) {
+    int best = i * starts;
+    for (int s2 = 1; s2 < starts; ++s2) {
+      const int v = i * starts + s2;
+      if (h[v].loss < h[best].loss) best = v;
+    }
+    o[i].defocus = ho[best].defocus;
+    o[i].na_det = ho[best].na_det;
+    o[i].tilt_zenith = ho[best].tilt_zenith;
+    o[i].tilt_azimuth = ho[best].tilt_azimuth;
+    if (loss_out) loss_out[i] = h[best].loss;
+    if (opts->all_theta_out)
+      for (int s2 = 0; s2 < starts; ++s2) {
+        const int v = i * starts + s2;
+        opts->all_theta_out[4 * v + 0] = ho[v].defocus;
+        opts->all_theta_out[4 * v + 1] = ho[v].na_det;
+        opts->all_theta_out[4 * v + 2] = ho[v].tilt_zenith;
+        opts->all_theta_out[4 * v + 3] = ho[v].tilt_azimuth;
+        if (opts->all_loss_out) opts->all_loss_out[v] = h[v].loss;
+      }
+  }
+  return WO_OK;
 }
 
 }  // extern "C"

@@ -1,0 +1,410 @@
+// Mid-band loss, its parameter gradient through the thin-model transfer
+// function, and the Adam auto-tune step (Results, "Physics-guided ML
+// auto-tunes multi-contrast blind deconvolution"; Methods, "Cell-scale optical
+// pooled screen data"; Ext. Data Fig. 3).
+//
+// Per iteration, for every (virtual) patch v with parameters theta_v =
+// (defocus, NA_det, tilt zenith, tilt azimuth):
+//   forward   A_z, B_z -> a, b (inverse 2D FFT) -> c = s b conj(a), s = N / I_bg
+//             H_z = [FFT2(2 Re c), FFT2(-2 Im c)]
+//             F = (H^H H + eta I)^-1 H^H D per 2D frequency (D = FFT2 of the stack)
+//             L = -(1/|B|) sum_{nu in band} |F_phase(nu)|^2
+//   backward  G_H = dL/dH* = r Y^H - (H Y) F^H, Y = M^-1 dL/dF*, r = D - H F
+//             Gamma = Re N IFFT2(G_phase) + i Re N IFFT2(G_abs)
+//             dL = 4 Re sum Gamma dc
+//                = 4 Re sum_p dB(p) IFFT2(s Gamma conj a)(p)
+//                + 4 Re sum_q dA(q) IFFT2(s conj(Gamma b))(q)
+//                + 4 Re sum Gamma b conj(a) ds
+//             with analytic dA/dtheta, dB/dtheta and dI_bg/dtheta.
+// The transfer function is recomputed every iteration, never stored across
+// iterations.
+#include "internal.hpp"
+
+namespace wo {
+
+// ------------------------------------------------------------------ helpers
+
+__device__ __forceinline__ double block_sum_d(double v, double* red) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  __syncthreads();
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0)
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += red[w];
+  return t;
+}
+
+// ------------------------------------------------------------------ loss and dL/dH*
+
+// One thread per half-spectrum frequency m = ky * Xh + kx of virtual patch v.
+// D: [n][Z][Y][Xh] (patch v reads data patch v / data_div), bank: [v][Z][2][Y][Xh],
+// overwritten with dL/dH*.  lpart[v * bpp + block] = sum of w |F_phase|^2.
+__global__ __launch_bounds__(256) void k_loss_grad(const DevOptics* __restrict__ opt,
+                                                   const TuneState* __restrict__ st, Sampling sm,
+                                                   const float2* __restrict__ D,
+                                                   float2* __restrict__ bank,
+                                                   double* __restrict__ lpart, long bpp,
+                                                   int data_div) {
+  __shared__ double red[4];
+  const int Z = sm.nz, Y = sm.ny, X = sm.nx, Xh = X / 2 + 1;
+  const long M = (long)Y * Xh;
+  const long v = blockIdx.x / bpp;
+  const long blk = blockIdx.x - v * bpp;
+  const long m = blk * blockDim.x + threadIdx.x;
+  double lsum = 0.0;
+  if (m < M) {
+    const int ky = (int)(m / Xh), kx = (int)(m - (long)ky * Xh);
+    const double fy = fftfreq(ky, Y, sm.dy), fx = fftfreq(kx, X, sm.dx);
+    const double r = sqrt(fy * fy + fx * fx);
+    const TuneState& s = st[v];
+    const bool band = r >= s.nu_c / 8.0 && r <= s.nu_c / 4.0;
+    const float eta = (float)s.eta;
+    const float2* dp = D + (v / data_div) * (long)Z * M + m;
+    float2* hp = bank + v * (long)Z * 2 * M + m;
+    // pass 1: normal matrix and right-hand side
+    float m00 = 0.f, m11 = 0.f;
+    float2 m10 = make_float2(0.f, 0.f), r0 = make_float2(0.f, 0.f), r1 = make_float2(0.f, 0.f);
+    for (int c = 0; c < Z; ++c) {
+      const float2 h0 = hp[(long)(2 * c) * M], h1 = hp[(long)(2 * c + 1) * M];
+      const float2 x = dp[(long)c * M];
+      m00 += h0.x * h0.x + h0.y * h0.y;
+      m11 += h1.x * h1.x + h1.y * h1.y;
+      m10 = cadd(m10, cmul(cconj(h1), h0));
+      r0 = cadd(r0, cmul(cconj(h0), x));
+      r1 = cadd(r1, cmul(cconj(h1), x));
+    }
+    const float a00 = m00 + eta, a11 = m11 + eta;
+    const float det = a00 * a11 - (m10.x * m10.x + m10.y * m10.y);
+    const float idet = 1.f / det;
+    // F = M^-1 r with M = [[a00, conj(m10)], [m10, a11]]
+    const float2 F0 = cscale(csub(cscale(r0, a11), cmul(cconj(m10), r1)), idet);
+    const float2 F1 = cscale(csub(cscale(r1, a00), cmul(m10, r0)), idet);
+    if (band) {
+      const double w = (kx == 0 || 2 * kx == X) ? 1.0 : 2.0;
+      lsum = w * ((double)F0.x * F0.x + (double)F0.y * F0.y);
+      const float ib = (float)(1.0 / s.band_count);
+      const float2 g0 = cscale(F0, -ib);                  // dL/dF_phase*
+      const float2 Y0 = cscale(cscale(g0, a11), idet);    // Y = M^-1 (g0, 0)
+      const float2 Y1 = cscale(cmul(m10, g0), -idet);
+      for (int c = 0; c < Z; ++c) {
+        const float2 h0 = hp[(long)(2 * c) * M], h1 = hp[(long)(2 * c + 1) * M];
+        const float2 x = dp[(long)c * M];
+        const float2 rc = csub(x, cadd(cmul(h0, F0), cmul(h1, F1)));
+        const float2 hy = cadd(cmul(h0, Y0), cmul(h1, Y1));
+        hp[(long)(2 * c) * M] = csub(cmulconj(rc, Y0), cmulconj(hy, F0));
+        hp[(long)(2 * c + 1) * M] = csub(cmulconj(rc, Y1), cmulconj(hy, F1));
+      }
+    } else {
+      for (int c = 0; c < 2 * Z; ++c) hp[(long)c * M] = make_float2(0.f, 0.f);
+    }
+  }
+  const double tot = block_sum_d(lsum, red);
+  if (threadIdx.x == 0) lpart[v * bpp + blk] = tot;
+}
+
+hipError_t launch_loss_grad(const DevOptics* opt, const TuneState* st, const Sampling& sm, int nv,
+                            const float2* D, float2* bank, double* lpart, int data_div,
+                            hipStream_t s) {
+  const long M = (long)sm.ny * (sm.nx / 2 + 1);
+  const long bpp = (M + 255) / 256;
+  { ScopedTiming _t("k_loss_grad", s);
+  hipLaunchKernelGGL(k_loss_grad, dim3((unsigned)(bpp * nv)), dim3(256), 0, s, opt, st, sm, D, bank,
+                     lpart, bpp, data_div); }
+  return hipGetLastError();
+}
+
+long loss_blocks(const Sampling& sm) {
+  const long M = (long)sm.ny * (sm.nx / 2 + 1);
+  return (M + 255) / 256;
+}
+
+// ------------------------------------------------------------------ backward rows
+
+// ab: [v][2][Z][Y][X] (field 0 = a, 1 = b after the inverse Y pass, complex);
+// gam: [v][Z][2][Y][X] real (Gamma phase, absorption).  Replaces field 0 by the
+// inverse X transform of u_A = conj(Gamma b)/(N I_bg) and field 1 by that of
+// u_B = Gamma conj(a)/(N I_bg); dpart[v * wpp + wg] = sum Re(Gamma b conj(a)).
+__global__ __launch_bounds__(1024) void k_tf_rows_bwd(const double* __restrict__ partials,
+                                                      long tiles_x, Sampling sm,
+                                                      float2* __restrict__ ab,
+                                                      const float* __restrict__ gam,
+                                                      double* __restrict__ dpart, int rows_per_wg,
+                                                      long wg_per_patch, FftPlan plan) {
+  extern __shared__ float2 smem[];
+  __shared__ double red[kMaxThreads / 64];
+  __shared__ double ibg_s;
+  const int Y = sm.ny, X = sm.nx, Z = sm.nz;
+  float2* tw = smem;
+  float2* buf = smem + X;
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  fill_twiddles(tw, X, tid, nthr);
+  const long v = blockIdx.x / wg_per_patch;
+  const long rpp = (long)Z * Y;
+  const long wg = blockIdx.x - v * wg_per_patch;
+  const long row0 = wg * (long)rows_per_wg;
+  const int nr = (int)min((long)rows_per_wg, rpp - row0);
+  float2* a_src = ab + (v * 2 + 0) * rpp * X;
+  float2* b_src = ab + (v * 2 + 1) * rpp * X;
+  if (tid == 0) {
+    double t = 0.0;
+    for (long i = 0; i < tiles_x; ++i) t += partials[v * tiles_x + i];
+    ibg_s = t;
+  }
+  gather_to_lds(buf, nr * 2 * X, tid, nthr, [&](int e) {
+    const int i = e % X;
+    const int t = e / X;
+    const int f = t & 1, r = t >> 1;
+    const float2* src = f ? b_src : a_src;
+    return src[(row0 + r) * X + i];
+  });
+  __syncthreads();
+  lds_fft(buf, LdsLines{2 * nr, 1, X, false}, plan, tw, 1.f, tid, nthr);
+  const float k = (float)(1.0 / ((double)X * (double)Y * ibg_s));
+  double dsum = 0.0;
+  for (int e = tid; e < nr * X; e += nthr) {
+    const int r = e / X, i = e - r * X;
+    const long row = row0 + r;
+    const long z = row / Y, y = row - z * Y;
+    const float gph = gam[(((v * Z + z) * 2 + 0) * (long)Y + y) * X + i];
+    const float gab = gam[(((v * Z + z) * 2 + 1) * (long)Y + y) * X + i];
+    const float2 G = make_float2(gph, gab);
+    const float2 a = buf[2 * r * X + i], b = buf[(2 * r + 1) * X + i];
+    const float2 gb = cmul(G, b);
+    dsum += (double)gb.x * a.x + (double)gb.y * a.y;     // Re(G b conj(a))
+    buf[2 * r * X + i] = cscale(cconj(gb), k);          // u_A
+    buf[(2 * r + 1) * X + i] = cscale(cmulconj(G, a), k);  // u_B
+  }
+  const double tot = block_sum_d(dsum, red);
+  if (tid == 0) dpart[v * wg_per_patch + wg] = tot;
+  __syncthreads();
+  lds_fft(buf, LdsLines{2 * nr, 1, X, false}, plan, tw, 1.f, tid, nthr);
+  scatter_from_lds(buf, nr * 2 * X, tid, nthr, [&](int e, float2 val) {
+    const int i = e % X;
+    const int t = e / X;
+    const int f = t & 1, r = t >> 1;
+    float2* dst = f ? b_src : a_src;
+    dst[(row0 + r) * X + i] = val;
+  });
+}
+
+int bwd_rows_per_wg(const Sampling& sm) {
+  int R = 2048 / sm.nx;
+  if (R < 1) R = 1;
+  while (R > 1 && 2L * R * sm.nx > kMaxElems) --R;
+  return R;
+}
+
+long bwd_wg_per_patch(const Sampling& sm) {
+  const int R = bwd_rows_per_wg(sm);
+  return ((long)sm.nz * sm.ny + R - 1) / R;
+}
+
+hipError_t launch_tf_rows_bwd(const double* partials, const Sampling& sm, int nv, float2* ab,
+                              const float* gam, double* dpart, hipStream_t s) {
+  FftPlan plan;
+  if (!make_plan(sm.nx, &plan)) return hipErrorInvalidValue;
+  const int R = bwd_rows_per_wg(sm);
+  const long wpp = bwd_wg_per_patch(sm);
+  const long tiles_x = (sm.nx + tf_tile_width(sm) - 1) / tf_tile_width(sm);
+  const int thr = threads_for(2L * R * sm.nx);
+  const size_t lds = (size_t)(sm.nx + 2 * R * sm.nx) * sizeof(float2);
+  { ScopedTiming _t("k_tf_rows_bwd", s);
+  hipLaunchKernelGGL(k_tf_rows_bwd, dim3((unsigned)(wpp * nv)), dim3(thr), lds, s, partials,
+                     tiles_x, sm, ab, gam, dpart, R, wpp, plan); }
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ backward columns + contraction
+
+// Inverse Y transform of u_A, u_B columns, then per lateral frequency the
+// contraction 4 Re(U_B dB/dtheta + U_A dA/dtheta).  gpart[((v*Z + z)*tiles + tile)*4 + j];
+// plane-0 workgroups also write dI_bg/dtheta partials to ipart[(v*tiles + tile)*4 + j].
+__global__ __launch_bounds__(1024) void k_tf_grad_y(const DevOptics* __restrict__ opt, Sampling sm,
+                                                    const float2* __restrict__ ab,
+                                                    double* __restrict__ gpart,
+                                                    double* __restrict__ ipart, int W,
+                                                    long tiles_x, FftPlan plan) {
+  extern __shared__ float2 smem[];
+  __shared__ double red[kMaxThreads / 64];
+  const int Y = sm.ny, X = sm.nx, Z = sm.nz;
+  float2* tw = smem;
+  float2* buf = smem + Y;
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  fill_twiddles(tw, Y, tid, nthr);
+  const long tile = blockIdx.x % tiles_x;
+  const long vz = blockIdx.x / tiles_x;
+  const int z = (int)(vz % Z);
+  const long v = vz / Z;
+  const DevOptics o = opt[v];
+  const int x0 = (int)(tile * W);
+  gather_to_lds(buf, Y * 2 * W, tid, nthr, [&](int e) {
+    const int ky = e / (2 * W);
+    const int r = e - ky * 2 * W;
+    const int f = r / W, w = r - f * W;
+    const int kx = x0 + w;
+    return kx < X ? ab[(((v * 2 + f) * Z + z) * (long)Y + ky) * X + kx] : make_float2(0.f, 0.f);
+  });
+  __syncthreads();
+  lds_fft(buf, LdsLines{2 * W, 2 * W, 1, true}, plan, tw, 1.f, tid, nthr);
+  const double hw = soft_halfwidth(o, sm);
+  const double km = o.n_medium / o.wavelength;
+  const double rd = o.na_det / o.wavelength, ri = o.na_ill / o.wavelength;
+  double cy, cx;
+  source_centre(o, &cy, &cx);
+  const double rq0 = o.n_medium * sin(o.tilt_zenith) / o.wavelength;
+  const double drq0 = o.n_medium * cos(o.tilt_zenith) / o.wavelength;
+  const double sa = sin(o.tilt_azimuth), ca = cos(o.tilt_azimuth);
+  const double dzr = plane_z(z, sm) - o.defocus;
+  double g[4] = {0.0, 0.0, 0.0, 0.0};
+  double di[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int e = tid; e < Y * W; e += nthr) {
+    const int ky = e / W, w = e - ky * W;
+    const int kx = x0 + w;
+    if (kx >= X) continue;
+    const double fy = fftfreq(ky, Y, sm.dy), fx = fftfreq(kx, X, sm.dx);
+    const double rp = sqrt(fy * fy + fx * fx);
+    const double P = disc(fy, fx, rd, hw);
+    const double dP = edge_slope(rd - rp, hw) / o.wavelength;     // dP / dNA_det
+    const double qy = fy - cy, qx = fx - cx;
+    const double rq = sqrt(qy * qy + qx * qx);
+    const double S = disc(qy, qx, ri, hw);
+    const double sl = edge_slope(ri - rq, hw);
+    const double uy = rq > 0.0 ? qy / rq : 0.0, ux = rq > 0.0 ? qx / rq : 0.0;
+    const double dSy = sl * uy, dSx = sl * ux;                     // dS / d(cy, cx)
+    const double dSz = dSy * drq0 * sa + dSx * drq0 * ca;          // dS / d zenith
+    const double dSa = dSy * rq0 * ca - dSx * rq0 * sa;            // dS / d azimuth
+    if (z == 0) {
+      di[1] += 2.0 * S * P * dP;
+      di[2] += dSz * P * P;
+      di[3] += dSa * P * P;
+    }
+    if (P == 0.0 && dP == 0.0) continue;
+    const double kz = sqrt(fmax(km * km - rp * rp, 0.0));
+    const double arg = 2.0 * kz * dzr;
+    const float red_arg = (float)(arg - 2.0 * rint(0.5 * arg));
+    float snf, csf;
+    sincospif(red_arg, &snf, &csf);
+    const double cs = csf, sn = snf;
+    const float2 UA = buf[ky * 2 * W + w];
+    const float2 UB = buf[ky * 2 * W + W + w];
+    // Re(U * q e^{i phi}) for a complex scalar q = (qr, qi)
+    const double ua_re = UA.x * cs - UA.y * sn, ua_im = UA.x * sn + UA.y * cs;   // U_A e^{i phi}
+    const double ub_re = UB.x * cs - UB.y * sn, ub_im = UB.x * sn + UB.y * cs;   // U_B e^{i phi}
+    // A = S P e, B = P (i km / kz) e; d/d defocus multiplies by -i 2 pi kz
+    const double gk = kz > 0.0 ? km / kz : 0.0;
+    const double tpk = 2.0 * M_PI * kz;
+    // Re(U_A A (-i tpk)) = tpk * S P * Im(U_A e)
+    // Re(U_B B (-i tpk)) = Re(U_B e * i gk P * (-i tpk)) = tpk gk P Re(U_B e)
+    g[0] += tpk * (S * P * ua_im + gk * P * ub_re);
+    // d/dNA: A' = S dP e, B' = dP i gk e -> Re(U_B e i gk dP) = -gk dP Im(U_B e)
+    g[1] += S * dP * ua_re - gk * dP * ub_im;
+    g[2] += dSz * P * ua_re;
+    g[3] += dSa * P * ua_re;
+  }
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const double t = block_sum_d(4.0 * g[j], red);
+    if (tid == 0) gpart[(vz * tiles_x + tile) * 4 + j] = t;
+  }
+  if (z == 0) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const double t = block_sum_d(di[j], red);
+      if (tid == 0) ipart[(v * tiles_x + tile) * 4 + j] = t;
+    }
+  }
+}
+
+hipError_t launch_tf_grad_y(const DevOptics* opt, const Sampling& sm, int nv, const float2* ab,
+                            double* gpart, double* ipart, hipStream_t s) {
+  FftPlan plan;
+  if (!make_plan(sm.ny, &plan)) return hipErrorInvalidValue;
+  const int W = tf_tile_width(sm);
+  const long tiles = (sm.nx + W - 1) / W;
+  const long nwg = tiles * sm.nz * (long)nv;
+  const int thr = threads_for((long)sm.ny * 2 * W);
+  const size_t lds = (size_t)(sm.ny + sm.ny * 2 * W) * sizeof(float2);
+  { ScopedTiming _t("k_tf_grad_y", s);
+  hipLaunchKernelGGL(k_tf_grad_y, dim3((unsigned)nwg), dim3(thr), lds, s, opt, sm, ab, gpart, ipart,
+                     W, tiles, plan); }
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ reduction + Adam
+
+// One workgroup per virtual patch: total loss and gradient from the partials,
+// then (if update) one Adam step with bias correction, mask and box.
+__global__ __launch_bounds__(256) void k_adam(DevOptics* __restrict__ opt,
+                                              TuneState* __restrict__ st, Sampling sm,
+                                              const double* __restrict__ ppart, long tiles_x,
+                                              const double* __restrict__ lpart, long lbpp,
+                                              const double* __restrict__ dpart, long dwpp,
+                                              const double* __restrict__ gpart,
+                                              const double* __restrict__ ipart, int update) {
+  __shared__ double red[4];
+  const long v = blockIdx.x;
+  const int tid = threadIdx.x;
+  double acc;
+  acc = 0.0;
+  for (long i = tid; i < lbpp; i += blockDim.x) acc += lpart[v * lbpp + i];
+  const double lsum = block_sum_d(acc, red);
+  acc = 0.0;
+  for (long i = tid; i < dwpp; i += blockDim.x) acc += dpart[v * dwpp + i];
+  const double dsum = block_sum_d(acc, red);
+  acc = 0.0;
+  for (long i = tid; i < tiles_x; i += blockDim.x) acc += ppart[v * tiles_x + i];
+  const double ibg = block_sum_d(acc, red);
+  double gj[4], dij[4];
+  const long gn = (long)sm.nz * tiles_x;
+  for (int j = 0; j < 4; ++j) {
+    acc = 0.0;
+    for (long i = tid; i < gn; i += blockDim.x) acc += gpart[(v * gn + i) * 4 + j];
+    gj[j] = block_sum_d(acc, red);
+    acc = 0.0;
+    for (long i = tid; i < tiles_x; i += blockDim.x) acc += ipart[(v * tiles_x + i) * 4 + j];
+    dij[j] = block_sum_d(acc, red);
+  }
+  if (tid != 0) return;
+  TuneState s = st[v];
+  const double N = (double)sm.ny * sm.nx;
+  const double loss = -lsum / s.band_count;
+  double grad[4];
+  for (int j = 0; j < 4; ++j) grad[j] = gj[j] - 4.0 * dsum / (N * ibg * ibg) * dij[j];
+  s.loss = loss;
+  for (int j = 0; j < 4; ++j) s.grad[j] = grad[j];
+  if (update) {
+    DevOptics o = opt[v];
+    double th[4] = {o.defocus, o.na_det, o.tilt_zenith, o.tilt_azimuth};
+    s.t += 1;
+    const double b1 = 0.9, b2 = 0.999, eps = 1e-8;
+    const double c1 = 1.0 - pow(b1, (double)s.t), c2 = 1.0 - pow(b2, (double)s.t);
+    for (int j = 0; j < 4; ++j) {
+      const double gm = ((s.mask >> j) & 1) ? grad[j] : 0.0;
+      s.m[j] = b1 * s.m[j] + (1.0 - b1) * gm;
+      s.v[j] = b2 * s.v[j] + (1.0 - b2) * gm * gm;
+      const double mh = s.m[j] / c1, vh = s.v[j] / c2;
+      double t = th[j] - s.lr[j] * mh / (sqrt(vh) + eps);
+      t = t < s.lo[j] ? s.lo[j] : (t > s.hi[j] ? s.hi[j] : t);
+      th[j] = t;
+    }
+    opt[v].defocus = th[0];
+    opt[v].na_det = th[1];
+    opt[v].tilt_zenith = th[2];
+    opt[v].tilt_azimuth = th[3];
+  }
+  st[v] = s;
+}
+
+hipError_t launch_adam(DevOptics* opt, TuneState* st, const Sampling& sm, int nv,
+                       const double* ppart, const double* lpart, const double* dpart,
+                       const double* gpart, const double* ipart, int update, hipStream_t s) {
+  const long tiles_x = (sm.nx + tf_tile_width(sm) - 1) / tf_tile_width(sm);
+  { ScopedTiming _t("k_adam", s);
+  hipLaunchKernelGGL(k_adam, dim3(nv), dim3(256), 0, s, opt, st, sm, ppart, tiles_x, lpart,
+                     loss_blocks(sm), dpart, bwd_wg_per_patch(sm), gpart, ipart, update); }
+  return hipGetLastError();
+}
+
+}  // namespace wo

@@ -291,6 +291,17 @@ struct DevOptics {
   double pad[3];
 };
 
+// Auto-tune state of one (virtual) patch: Adam moments and hyper-parameters,
+// Tikhonov eta, the mid-band cutoff and band size, and the last loss/gradient.
+struct TuneState {
+  double m[4], v[4];
+  double lr[4], lo[4], hi[4];
+  double eta, nu_c, band_count;
+  double loss, grad[4];
+  int t, mask;
+  int pad[2];
+};
+
 // Sampling shared by every patch of a call.
 struct Sampling {
   int model;

@@ -73,4 +73,19 @@ hipError_t launch_tf_rows_fluor(const double* partials, const Sampling& sm, int 
 hipError_t launch_tf_pol5_z(const DevOptics* opt, const Sampling& sm, int npatch, float2* uw,
                             float2* tf, hipStream_t s);
 
+// Auto-tune (thin model).
+hipError_t launch_set_tune(TuneState* dst, const TuneState* host, int n, hipStream_t s);
+long loss_blocks(const Sampling& sm);
+long bwd_wg_per_patch(const Sampling& sm);
+hipError_t launch_loss_grad(const DevOptics* opt, const TuneState* st, const Sampling& sm, int nv,
+                            const float2* D, float2* bank, double* lpart, int data_div,
+                            hipStream_t s);
+hipError_t launch_tf_rows_bwd(const double* partials, const Sampling& sm, int nv, float2* ab,
+                              const float* gam, double* dpart, hipStream_t s);
+hipError_t launch_tf_grad_y(const DevOptics* opt, const Sampling& sm, int nv, const float2* ab,
+                            double* gpart, double* ipart, hipStream_t s);
+hipError_t launch_adam(DevOptics* opt, TuneState* st, const Sampling& sm, int nv,
+                       const double* ppart, const double* lpart, const double* dpart,
+                       const double* gpart, const double* ipart, int update, hipStream_t s);
+
 }  // namespace wo

@@ -40,6 +40,28 @@ hipError_t launch_set_params(DevOptics* dst, const DevOptics* host, int n, hipSt
   return hipSuccess;
 }
 
+struct TuneBatch {
+  TuneState t[8];
+};
+static_assert(sizeof(TuneBatch) <= 3584, "kernel arguments are limited to 4 KiB");
+
+__global__ void k_set_tune(TuneState* dst, TuneBatch b, int count) {
+  const int i = threadIdx.x;
+  if (i < count) dst[i] = b.t[i];
+}
+
+hipError_t launch_set_tune(TuneState* dst, const TuneState* host, int n, hipStream_t s) {
+  for (int i0 = 0; i0 < n; i0 += 8) {
+    TuneBatch b;
+    const int cnt = n - i0 < 8 ? n - i0 : 8;
+    for (int j = 0; j < cnt; ++j) b.t[j] = host[i0 + j];
+    hipLaunchKernelGGL(k_set_tune, dim3(1), dim3(64), 0, s, dst + i0, b, cnt);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 // ------------------------------------------------------------------ reductions
 
 // Deterministic workgroup sum of one double per thread (wave shuffles, then
