@@ -33,4 +33,4 @@ value printed in the paper (parity unpinned; judged against synthetic ground
 truth only).
 """
 
-from . import optics, tf, linear, autotune  # noqa: F401
+from . import optics, tf, linear, autotune, cnn  # noqa: F401
