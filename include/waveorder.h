@@ -184,6 +184,54 @@ int wo_autotune(wo_optics* o, int32_t n, const float* d, const double* eta,
                 const wo_autotune_opts* opts, double* loss_out, void* ws, size_t ws_bytes,
                 void* stream);
 
+/* ---------------------------------------------------------------- learned initialiser
+ * Not in the paper: a small 3D CNN that regresses normalised (defocus, NA_det,
+ * tilt_zenith) from a defocus stack, used to start the auto-tune.  4 blocks of
+ * [3x3x3 convolution, stride 2, padding 1, bias, GELU] with channels
+ * 1 -> 32 -> 64 -> 128 -> 256, global average pooling, linear head to 3
+ * outputs; loss mean((y - t)^2); AdamW.  Convolutions run as implicit GEMMs on
+ * BF16 MFMA with FP32 accumulation; activations are BF16, parameters FP32
+ * (a BF16 copy of the weights feeds the MFMA).
+ * Parameter layout (flat FP32): for each block, weights [Cout][3][3][3][Cin]
+ * then bias [Cout]; then head weights [3][256] and bias [3].
+ * Inputs x: device [batch][nz][ny][nx] FP32 stacks; each sample is scaled by
+ * its RMS before the first convolution. */
+int64_t wo_cnn_param_count(void);
+size_t wo_cnn_workspace_size(int32_t batch, int32_t nz, int32_t ny, int32_t nx);
+/* y_out: device [batch][3]. */
+int wo_cnn_forward(const float* params, const float* x, int32_t batch, int32_t nz, int32_t ny,
+                   int32_t nx, float* y_out, void* ws, size_t ws_bytes, void* stream);
+/* Forward, loss (device scalar) and gradient (device flat FP32, or NULL to keep
+ * it in the workspace) for targets [batch][3]. */
+int wo_cnn_gradient(const float* params, const float* x, const float* target, int32_t batch,
+                    int32_t nz, int32_t ny, int32_t nx, float* y_out, float* loss_out,
+                    float* grad_out, void* ws, size_t ws_bytes, void* stream);
+/* One AdamW step (step t >= 1, beta 0.9/0.999, eps 1e-8, decoupled weight decay)
+ * on params with moments adam_m, adam_v (device, param_count floats each). */
+int wo_cnn_train_step(float* params, float* adam_m, float* adam_v, int32_t t, double lr,
+                      double weight_decay, const float* x, const float* target, int32_t batch,
+                      int32_t nz, int32_t ny, int32_t nx, float* y_out, float* loss_out, void* ws,
+                      size_t ws_bytes, void* stream);
+/* Single strided (2) 3x3x3 convolutions with padding 1 on BF16 operands (raw
+ * 16-bit storage), channels-last x [N][D][H][W][Cin], weights [Cout][27][Cin]:
+ * forward out [N][Do][Ho][Wo][Cout] (no bias), input gradient from
+ * gz [N][Do][Ho][Wo][Cout] to out [N][D][H][W][Cin], weight gradient
+ * out [Cout][27][Cin] (ws: FP32 split-K partials).  Do = (D - 1)/2 + 1. */
+int wo_conv3d_forward(const uint16_t* x, const uint16_t* w, int32_t N, int32_t D, int32_t H,
+                      int32_t W, int32_t Cin, int32_t Cout, float* out, void* stream);
+int wo_conv3d_input_grad(const uint16_t* gz, const uint16_t* w, int32_t N, int32_t D, int32_t H,
+                         int32_t W, int32_t Cin, int32_t Cout, float* out, void* stream);
+int wo_conv3d_weight_grad(const uint16_t* x, const uint16_t* gz, int32_t N, int32_t D, int32_t H,
+                          int32_t W, int32_t Cin, int32_t Cout, float* out, void* ws,
+                          size_t ws_bytes, void* stream);
+/* Training data for the learned initialiser (counter-based hashing, so the
+ * same seed gives the same data): thin cells out [n][2][ny][nx] (phase,
+ * absorption) with semi-axes U(0.8, 2.5) um, phase U(0.1, 0.5), absorption
+ * U(0, 0.02); and in-place additive Gaussian noise. */
+int wo_synth_thin_cells(float* out, int32_t n, int32_t ny, int32_t nx, double pixel, int32_t ncells,
+                        uint64_t seed, void* stream);
+int wo_add_gaussian_noise(float* x, int64_t n, double sigma, uint64_t seed, void* stream);
+
 /* Instrumentation (not part of the method): while enabled, every kernel the
  * library launches is bracketed by HIP events on the stream it runs on.
  * wo_timing_report() waits for the recorded events, writes one line

@@ -31,7 +31,10 @@ OP_ADJOINT = 3
 
 SYMBOLS = ("wo_bank_shape", "wo_workspace_size", "wo_transfer_function", "wo_forward",
            "wo_reconstruct", "wo_adjoint", "wo_strerror", "wo_version", "wo_timing_enable",
-           "wo_timing_report", "wo_tune_workspace_size", "wo_midband_loss_grad", "wo_autotune")
+           "wo_timing_report", "wo_tune_workspace_size", "wo_midband_loss_grad", "wo_autotune",
+           "wo_cnn_param_count", "wo_cnn_workspace_size", "wo_cnn_forward", "wo_cnn_gradient",
+           "wo_cnn_train_step", "wo_conv3d_forward", "wo_conv3d_input_grad", "wo_conv3d_weight_grad",
+           "wo_synth_thin_cells", "wo_add_gaussian_noise")
 
 _FIELDS = ("model", "nz", "ny", "nx", "dz", "dy", "dx", "wavelength", "na_ill", "na_det",
            "n_medium", "defocus", "tilt_zenith", "tilt_azimuth", "edge_width", "swing")
@@ -109,6 +112,20 @@ def load(path: str = LIB_PATH):
     lib.wo_tune_workspace_size.restype = sz
     lib.wo_midband_loss_grad.argtypes = [op, i32, vp, dp, dp, dp, dp, vp, sz, vp]
     lib.wo_autotune.argtypes = [op, i32, vp, dp, ctypes.POINTER(WoAutotuneOpts), dp, vp, sz, vp]
+    i64, u64, f64 = ctypes.c_int64, ctypes.c_uint64, ctypes.c_double
+    lib.wo_cnn_param_count.restype = i64
+    lib.wo_cnn_workspace_size.argtypes = [i32, i32, i32, i32]
+    lib.wo_cnn_workspace_size.restype = sz
+    lib.wo_cnn_forward.argtypes = [vp, vp, i32, i32, i32, i32, vp, vp, sz, vp]
+    lib.wo_cnn_gradient.argtypes = [vp, vp, vp, i32, i32, i32, i32, vp, vp, vp, vp, sz, vp]
+    lib.wo_cnn_train_step.argtypes = [vp, vp, vp, i32, f64, f64, vp, vp, i32, i32, i32, i32, vp, vp, vp,
+                                      sz, vp]
+    conv = [vp, vp, i32, i32, i32, i32, i32, i32, vp]
+    lib.wo_conv3d_forward.argtypes = conv + [vp]
+    lib.wo_conv3d_input_grad.argtypes = conv + [vp]
+    lib.wo_conv3d_weight_grad.argtypes = conv + [vp, sz, vp]
+    lib.wo_synth_thin_cells.argtypes = [vp, i32, i32, i32, f64, i32, u64, vp]
+    lib.wo_add_gaussian_noise.argtypes = [vp, i64, f64, u64, vp]
     lib.wo_timing_enable.argtypes = [ctypes.c_int]
     lib.wo_timing_report.argtypes = [ctypes.c_char_p, ctypes.c_size_t]
     for name in SYMBOLS:
@@ -398,3 +415,96 @@ def linear_forward_fn(f, optics, tf, b=None):
 def midband_loss_fn(theta, optics, d, eta, nu_c=None):
     """Differentiable mid-band loss in theta (backward = hand-written TF gradient)."""
     return _autograd()[1].apply(theta, optics, d, eta, nu_c)
+
+
+# ---------------------------------------------------------------- CNN and training data
+
+def cnn_param_count() -> int:
+    return int(load().wo_cnn_param_count())
+
+
+def cnn_workspace(batch, shape, device):
+    import torch
+    n = int(load().wo_cnn_workspace_size(batch, *shape))
+    return torch.empty(n, dtype=torch.uint8, device=device)
+
+
+def cnn_forward(params, x, ws=None, stream=None):
+    """y = CNN(x): params FP32 flat (device), x (batch, Z, Y, X) FP32 -> (batch, 3)."""
+    import torch
+    x = x.contiguous()
+    B = x.shape[0]
+    if ws is None:
+        ws = cnn_workspace(B, x.shape[1:], x.device)
+    y = torch.empty((B, 3), dtype=torch.float32, device=x.device)
+    _check(load().wo_cnn_forward(_ptr(params), _ptr(x), B, *x.shape[1:], _ptr(y), _ptr(ws), ws.numel(),
+                                 _stream(stream)), "wo_cnn_forward")
+    return y
+
+
+def cnn_gradient(params, x, target, ws=None, stream=None):
+    """(y, loss, grad) of the MSE loss for a batch."""
+    import torch
+    x = x.contiguous()
+    B = x.shape[0]
+    if ws is None:
+        ws = cnn_workspace(B, x.shape[1:], x.device)
+    y = torch.empty((B, 3), dtype=torch.float32, device=x.device)
+    loss = torch.empty(1, dtype=torch.float32, device=x.device)
+    grad = torch.empty_like(params)
+    _check(load().wo_cnn_gradient(_ptr(params), _ptr(x), _ptr(target.contiguous()), B, *x.shape[1:],
+                                  _ptr(y), _ptr(loss), _ptr(grad), _ptr(ws), ws.numel(), _stream(stream)),
+           "wo_cnn_gradient")
+    return y, loss, grad
+
+
+def cnn_train_step(params, m, v, t, lr, wd, x, target, ws, y, loss, stream=None):
+    _check(load().wo_cnn_train_step(_ptr(params), _ptr(m), _ptr(v), int(t), float(lr), float(wd), _ptr(x),
+                                    _ptr(target), x.shape[0], *x.shape[1:], _ptr(y), _ptr(loss), _ptr(ws),
+                                    ws.numel(), _stream(stream)), "wo_cnn_train_step")
+
+
+def conv3d_forward(x_bf16, w_bf16, cout, stream=None):
+    """x (N, D, H, W, Cin) and w (Cout, 27*Cin) as int16 BF16 bit patterns -> FP32 output."""
+    import torch
+    N, D, H, W, Cin = x_bf16.shape
+    out = torch.empty((N, (D - 1) // 2 + 1, (H - 1) // 2 + 1, (W - 1) // 2 + 1, cout),
+                      dtype=torch.float32, device=x_bf16.device)
+    _check(load().wo_conv3d_forward(_ptr(x_bf16), _ptr(w_bf16), N, D, H, W, Cin, cout, _ptr(out),
+                                    _stream(stream)), "wo_conv3d_forward")
+    return out
+
+
+def conv3d_input_grad(gz_bf16, w_bf16, in_shape, stream=None):
+    import torch
+    N, D, H, W, Cin = in_shape
+    cout = gz_bf16.shape[-1]
+    out = torch.empty(in_shape, dtype=torch.float32, device=gz_bf16.device)
+    _check(load().wo_conv3d_input_grad(_ptr(gz_bf16), _ptr(w_bf16), N, D, H, W, Cin, cout, _ptr(out),
+                                       _stream(stream)), "wo_conv3d_input_grad")
+    return out
+
+
+def conv3d_weight_grad(x_bf16, gz_bf16, stream=None):
+    import torch
+    N, D, H, W, Cin = x_bf16.shape
+    cout = gz_bf16.shape[-1]
+    out = torch.empty((cout, 27 * Cin), dtype=torch.float32, device=x_bf16.device)
+    ws = torch.empty(64 << 20, dtype=torch.uint8, device=x_bf16.device)
+    _check(load().wo_conv3d_weight_grad(_ptr(x_bf16), _ptr(gz_bf16), N, D, H, W, Cin, cout, _ptr(out),
+                                        _ptr(ws), ws.numel(), _stream(stream)), "wo_conv3d_weight_grad")
+    return out
+
+
+def synth_thin_cells(n, ny, nx, pixel, ncells, seed, device="cuda", stream=None):
+    import torch
+    out = torch.empty((n, 2, ny, nx), dtype=torch.float32, device=device)
+    _check(load().wo_synth_thin_cells(_ptr(out), n, ny, nx, float(pixel), int(ncells), int(seed),
+                                      _stream(stream)), "wo_synth_thin_cells")
+    return out
+
+
+def add_gaussian_noise(x, sigma, seed, stream=None):
+    _check(load().wo_add_gaussian_noise(_ptr(x), x.numel(), float(sigma), int(seed), _stream(stream)),
+           "wo_add_gaussian_noise")
+    return x

@@ -1,0 +1,801 @@
+// Parameter-regression CNN on BF16 MFMA (gfx950): the learned initialiser of
+// the auto-tune.  4 blocks of [3x3x3 convolution, stride 2, padding 1, bias,
+// GELU] (channels 1 -> 32 -> 64 -> 128 -> 256), global average pooling and a
+// linear head to 3 normalised parameters; MSE loss; AdamW.
+//
+// Every convolution (forward, input gradient, weight gradient) is one
+// implicit GEMM on v_mfma_f32_16x16x32_bf16 with FP32 accumulation:
+//   forward  C[pos_out][co]  = sum_{tap,ci} x(im2col)        * w[co][tap][ci]
+//   dgrad    C[pos_in][ci]   = sum_{tap,co} gz(col2im)       * w[co][tap][ci]
+//   wgrad    C[co][tap,ci]   = sum_{pos_out} gz[pos_out][co] * x(im2col)
+// Operands are gathered on the fly into LDS tiles (no im2col buffer).
+// Activations are channels-last BF16, pre-activations FP32.
+// Lane layout of the 16x16x32 MFMA (checked on the device): lane l holds
+// A[l%16][(l/16)*8 + i] and B[(l/16)*8 + i][l%16], i < 8; accumulator
+// register r of lane l is C[(l/16)*4 + r][l%16].
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "../../include/waveorder.h"
+#include "internal.hpp"
+
+namespace wo {
+
+typedef unsigned short u16;
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ u16 f2bf(float f) {  // round to nearest even
+  unsigned u = __float_as_uint(f);
+  if ((u & 0x7f800000u) == 0x7f800000u) return (u16)(u >> 16);  // inf / nan
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (u16)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(u16 b) { return __uint_as_float(((unsigned)b) << 16); }
+
+// ------------------------------------------------------------------ operand gathers
+//
+// A gather exposes row(i) -> a per-row context computed once per kernel (the
+// thread's row of the tile never changes), then at(ctx, k) for the K index.
+// K indices walk (tap, channel) with the channel fastest.
+
+struct ConvGeom {
+  int D, H, W, C;     // input volume and channels
+  int Do, Ho, Wo;     // output volume
+};
+
+struct TapCh {  // (tap, channel) of a K index, advanced incrementally
+  int tap, ch;
+};
+
+// A(m, k) of the forward GEMM: m = output position, k = tap * Cin + ci.
+struct GatherIm2col {
+  const u16* x;
+  ConvGeom g;
+  struct Row { long n; int d0, h0, w0; };
+  __device__ __forceinline__ Row row(long m) const {
+    Row r;
+    long q = m;
+    const int ow = (int)(q % g.Wo); q /= g.Wo;
+    const int oh = (int)(q % g.Ho); q /= g.Ho;
+    const int od = (int)(q % g.Do);
+    r.n = q / g.Do;
+    r.d0 = 2 * od - 1; r.h0 = 2 * oh - 1; r.w0 = 2 * ow - 1;
+    return r;
+  }
+  __device__ __forceinline__ int chans() const { return g.C; }
+  __device__ __forceinline__ u16 at(const Row& r, TapCh t) const {
+    const int kw = t.tap % 3, kh = (t.tap / 3) % 3, kd = t.tap / 9;
+    const int id = r.d0 + kd, ih = r.h0 + kh, iw = r.w0 + kw;
+    if (id < 0 || id >= g.D || ih < 0 || ih >= g.H || iw < 0 || iw >= g.W) return 0;
+    return x[(((r.n * g.D + id) * g.H + ih) * g.W + iw) * g.C + t.ch];
+  }
+};
+
+// B(k, n) = w[n * K + k] (weights stored [Cout][tap][Cin]).
+struct GatherRows {
+  const u16* w;
+  long K;
+  int C;  // channels per tap along k
+  struct Row { const u16* p; };
+  __device__ __forceinline__ Row row(long n) const { return Row{w + n * K}; }
+  __device__ __forceinline__ int chans() const { return C; }
+  __device__ __forceinline__ u16 at(const Row& r, TapCh t) const { return r.p[(long)t.tap * C + t.ch]; }
+};
+
+// A(m, k) of the input-gradient GEMM restricted to one parity class of input
+// positions (pd, ph, pw): m enumerates the class, k = j * Cout + co runs over
+// the taps that reach an output position from this class (kd = 1 for even d,
+// kd in {0, 2} for odd d, per axis).
+struct GatherCol2imClass {
+  const u16* gz;
+  ConvGeom g;     // g.C = Cout
+  int pd, ph, pw; // parity of the class
+  int cd, ch, cw; // class extents: positions with that parity
+  int nd, nh, nw; // valid taps per axis (1 or 2)
+  struct Row { long n; int d, h, w; };
+  __device__ __forceinline__ Row row(long m) const {
+    Row r;
+    long q = m;
+    const int iw = (int)(q % cw); q /= cw;
+    const int ih = (int)(q % ch); q /= ch;
+    const int id = (int)(q % cd);
+    r.n = q / cd;
+    r.d = 2 * id + pd; r.h = 2 * ih + ph; r.w = 2 * iw + pw;
+    return r;
+  }
+  __device__ __forceinline__ int chans() const { return g.C; }
+  __device__ __forceinline__ u16 at(const Row& r, TapCh t) const {
+    const int jw = t.tap % nw, jh = (t.tap / nw) % nh, jd = t.tap / (nw * nh);
+    const int kd = nd == 1 ? 1 : 2 * jd, kh = nh == 1 ? 1 : 2 * jh, kw = nw == 1 ? 1 : 2 * jw;
+    const int od2 = r.d + 1 - kd, oh2 = r.h + 1 - kh, ow2 = r.w + 1 - kw;
+    if (od2 < 0 || oh2 < 0 || ow2 < 0) return 0;
+    const int od = od2 >> 1, oh = oh2 >> 1, ow = ow2 >> 1;
+    if (od >= g.Do || oh >= g.Ho || ow >= g.Wo) return 0;
+    return gz[(((r.n * g.Do + od) * g.Ho + oh) * g.Wo + ow) * g.C + t.ch];
+  }
+  // the global input position of class row m (output row mapping)
+  __device__ __forceinline__ long out_row(long m) const {
+    const Row r = row(m);
+    return ((r.n * g.D + r.d) * g.H + r.h) * g.W + r.w;
+  }
+};
+
+// B(k, n) of the class input-gradient GEMM: w[co][tap(j)][ci], k = j * Cout + co, n = ci.
+struct GatherWTClass {
+  const u16* w;
+  int Cin, Cout;
+  int nd, nh, nw;
+  struct Row { int ci; };
+  __device__ __forceinline__ Row row(long n) const { return Row{(int)n}; }
+  __device__ __forceinline__ int chans() const { return Cout; }
+  __device__ __forceinline__ u16 at(const Row& r, TapCh t) const {
+    const int jw = t.tap % nw, jh = (t.tap / nw) % nh, jd = t.tap / (nw * nh);
+    const int kd = nd == 1 ? 1 : 2 * jd, kh = nh == 1 ? 1 : 2 * jh, kw = nw == 1 ? 1 : 2 * jw;
+    const int tap = (kd * 3 + kh) * 3 + kw;
+    return w[((long)t.ch * 27 + tap) * Cin + r.ci];
+  }
+};
+
+// A(m, k) of the weight-gradient GEMM: gz[k][m] (k = output position, m = co).
+// K here is a position index (chans() = 1, tap = position).
+struct GatherT {
+  const u16* gz;
+  int Cout;
+  struct Row { int co; };
+  __device__ __forceinline__ Row row(long m) const { return Row{(int)m}; }
+  __device__ __forceinline__ int chans() const { return 1; }
+  __device__ __forceinline__ u16 at(const Row& r, TapCh t) const { return gz[(long)t.tap * Cout + r.co]; }
+};
+
+// B(k, n) of the weight-gradient GEMM: im2col(x)(position k, n = tap * Cin + ci).
+struct GatherIm2colT {
+  GatherIm2col a;
+  struct Row { int tap, ci; };
+  __device__ __forceinline__ Row row(long n) const { return Row{(int)(n / a.g.C), (int)(n % a.g.C)}; }
+  __device__ __forceinline__ int chans() const { return 1; }
+  __device__ __forceinline__ u16 at(const Row& r, TapCh t) const {
+    return a.at(a.row(t.tap), TapCh{r.tap, r.ci});
+  }
+};
+
+struct IdentityRows {
+  __device__ __forceinline__ long operator()(long m) const { return m; }
+};
+struct ClassRows {
+  GatherCol2imClass c;
+  __device__ __forceinline__ long operator()(long m) const { return c.out_row(m); }
+};
+
+// ------------------------------------------------------------------ GEMM
+
+constexpr int kBM = 64, kBN = 64, kBK = 32, kLdsPad = 8;
+
+// C_z[rowmap(m)][n] = sum_{k in chunk z} A(m, k) B(k, n); C_z = C + z * Mout * N.
+template <class GA, class GB, class RM>
+__global__ __launch_bounds__(256) void k_gemm_bf16(GA ga, GB gb, RM rowmap, float* __restrict__ C,
+                                                   long M, long N, long K, long kchunk, long Mout) {
+  __shared__ __attribute__((aligned(16))) u16 As[kBM][kBK + kLdsPad];
+  __shared__ __attribute__((aligned(16))) u16 Bs[kBN][kBK + kLdsPad];
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const long m0 = (long)blockIdx.x * kBM, n0 = (long)blockIdx.y * kBN;
+  const long kbeg = (long)blockIdx.z * kchunk;
+  const long kend = min(K, kbeg + kchunk);
+  f32x4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const int lr = t >> 2, lk = (t & 3) * 8;
+  const bool am = m0 + lr < M, bn = n0 + lr < N;
+  const typename GA::Row ra = ga.row(am ? m0 + lr : 0);
+  const typename GB::Row rb = gb.row(bn ? n0 + lr : 0);
+  const int ca = ga.chans(), cb = gb.chans();
+  for (long k0 = kbeg; k0 < kend; k0 += kBK) {
+    const long kf = k0 + lk;
+    TapCh ta{(int)(kf / ca), (int)(kf % ca)};
+    TapCh tb{(int)(kf / cb), (int)(kf % cb)};
+    u16 va[8], vb[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const bool kin = kf + i < kend;
+      va[i] = (am && kin) ? ga.at(ra, ta) : (u16)0;
+      vb[i] = (bn && kin) ? gb.at(rb, tb) : (u16)0;
+      if (++ta.ch == ca) { ta.ch = 0; ++ta.tap; }
+      if (++tb.ch == cb) { tb.ch = 0; ++tb.tap; }
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      As[lr][lk + i] = va[i];
+      Bs[lr][lk + i] = vb[i];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const bf16x8 a = *(const bf16x8*)&As[wm * 32 + i * 16 + (lane & 15)][(lane >> 4) * 8];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const bf16x8 b = *(const bf16x8*)&Bs[wn * 32 + j * 16 + (lane & 15)][(lane >> 4) * 8];
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[i][j], 0, 0, 0);
+      }
+    }
+    __syncthreads();
+  }
+  float* Cz = C + (long)blockIdx.z * Mout * N;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const long row = m0 + wm * 32 + i * 16 + (lane >> 4) * 4 + r;
+      if (row >= M) continue;
+      const long orow = rowmap(row);
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const long col = n0 + wn * 32 + j * 16 + (lane & 15);
+        if (col < N) Cz[orow * N + col] = acc[i][j][r];
+      }
+    }
+}
+
+template <class GA, class GB, class RM = IdentityRows>
+static hipError_t gemm(GA ga, GB gb, float* C, long M, long N, long K, int splits, hipStream_t s,
+                       const char* tag, RM rowmap = RM(), long Mout = -1) {
+  long kchunk = (K + splits - 1) / splits;
+  kchunk = (kchunk + kBK - 1) / kBK * kBK;
+  const int z = (int)((K + kchunk - 1) / kchunk);
+  dim3 grid((unsigned)((M + kBM - 1) / kBM), (unsigned)((N + kBN - 1) / kBN), (unsigned)z);
+  { ScopedTiming _t(tag, s);
+  hipLaunchKernelGGL((k_gemm_bf16<GA, GB, RM>), grid, dim3(256), 0, s, ga, gb, rowmap, C, M, N, K,
+                     kchunk, Mout < 0 ? M : Mout); }
+  return hipGetLastError();
+}
+
+// Input gradient as 8 GEMMs, one per parity class of input positions.
+static hipError_t dgrad_classes(const u16* gz, const u16* w, ConvGeom gout, int Cin, int N,
+                                float* out, hipStream_t s) {
+  for (int cls = 0; cls < 8; ++cls) {
+    GatherCol2imClass a;
+    a.gz = gz;
+    a.g = gout;
+    a.pd = cls >> 2; a.ph = (cls >> 1) & 1; a.pw = cls & 1;
+    a.cd = (gout.D - a.pd + 1) / 2; a.ch = (gout.H - a.ph + 1) / 2; a.cw = (gout.W - a.pw + 1) / 2;
+    if (a.cd <= 0 || a.ch <= 0 || a.cw <= 0) continue;
+    a.nd = a.pd ? 2 : 1; a.nh = a.ph ? 2 : 1; a.nw = a.pw ? 2 : 1;
+    const long M = (long)N * a.cd * a.ch * a.cw;
+    const long K = (long)a.nd * a.nh * a.nw * gout.C;
+    GatherWTClass b{w, Cin, gout.C, a.nd, a.nh, a.nw};
+    hipError_t e = gemm(a, b, out, M, Cin, K, 1, s, "k_gemm_conv_dgrad", ClassRows{a},
+                        (long)N * gout.D * gout.H * gout.W);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+static int splits_used(long K, int splits) {
+  long kchunk = (K + splits - 1) / splits;
+  kchunk = (kchunk + kBK - 1) / kBK * kBK;
+  return (int)((K + kchunk - 1) / kchunk);
+}
+
+// out[i] = sum_z part[z * n + i] (fixed order)
+__global__ void k_sum_splits(const float* __restrict__ part, int z, long n, float* __restrict__ out) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  float s = 0.f;
+  for (int q = 0; q < z; ++q) s += part[q * n + i];
+  out[i] = s;
+}
+
+// ------------------------------------------------------------------ elementwise
+
+__device__ __forceinline__ float gelu_f(float z) { return 0.5f * z * (1.f + erff(z * 0.70710678118654752f)); }
+__device__ __forceinline__ float gelu_grad_f(float z) {
+  return 0.5f * (1.f + erff(z * 0.70710678118654752f)) + z * expf(-0.5f * z * z) * 0.39894228040143268f;
+}
+
+// z = C + b[c] (FP32), a = BF16(GELU(z)); C and z may alias.
+__global__ void k_bias_gelu(const float* C, const float* __restrict__ b, long P, int Co, float* z,
+                            u16* __restrict__ a) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= P * Co) return;
+  const float v = C[i] + b[i % Co];
+  z[i] = v;
+  a[i] = f2bf(gelu_f(v));
+}
+
+// gz = BF16(ga * GELU'(z))
+__global__ void k_gelu_bwd(const float* __restrict__ ga, const float* __restrict__ z, long n,
+                           u16* __restrict__ gz) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  gz[i] = f2bf(ga[i] * gelu_grad_f(z[i]));
+}
+
+// gb[c] = sum_p gz[p][c], one workgroup per channel (fixed order)
+__global__ __launch_bounds__(256) void k_bias_grad(const u16* __restrict__ gz, long P, int Co,
+                                                   float* __restrict__ gb) {
+  __shared__ float red[256];
+  const int c = blockIdx.x;
+  float s = 0.f;
+  for (long p = threadIdx.x; p < P; p += blockDim.x) s += bf2f(gz[p * Co + c]);
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) gb[c] = red[0];
+}
+
+// Per-sample input scaling x / rms(x) -> BF16 channels-last (C = 1).
+__global__ __launch_bounds__(256) void k_normalise(const float* __restrict__ x, long vol,
+                                                   u16* __restrict__ out) {
+  __shared__ double red[256];
+  const long n = blockIdx.x;
+  const float* xs = x + n * vol;
+  double s = 0.0;
+  for (long i = threadIdx.x; i < vol; i += blockDim.x) s += (double)xs[i] * xs[i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+    __syncthreads();
+  }
+  const double rms = sqrt(red[0] / (double)vol);
+  const float inv = rms > 0.0 ? (float)(1.0 / rms) : 1.f;
+  for (long i = threadIdx.x; i < vol; i += blockDim.x) out[n * vol + i] = f2bf(xs[i] * inv);
+}
+
+// Head per sample: feat = mean over positions of a (BF16), y = Wh feat + bh.
+// With targets: dy = 2 (y - t) / (3 N), lossp[n] = sum (y - t)^2, and
+// ga[n][p][c] = (Wh^T dy)[c] / npos.
+__global__ __launch_bounds__(256) void k_head(const u16* __restrict__ a, long npos, int Cf,
+                                              const float* __restrict__ wh, const float* __restrict__ bh,
+                                              const float* __restrict__ target, int N,
+                                              float* __restrict__ y_out, float* __restrict__ feat_out,
+                                              float* __restrict__ dy_out, float* __restrict__ lossp,
+                                              float* __restrict__ ga) {
+  __shared__ float feat[256];
+  __shared__ float dys[kCnnOut];
+  const int n = blockIdx.x, c = threadIdx.x;
+  if (c < Cf) {
+    float s = 0.f;
+    for (long p = 0; p < npos; ++p) s += bf2f(a[((long)n * npos + p) * Cf + c]);
+    feat[c] = s / (float)npos;
+    if (feat_out) feat_out[(long)n * Cf + c] = feat[c];
+  }
+  __syncthreads();
+  if (c < kCnnOut) {
+    float y = bh[c];
+    for (int k = 0; k < Cf; ++k) y += wh[c * Cf + k] * feat[k];
+    y_out[n * kCnnOut + c] = y;
+    if (target) {
+      const float d = y - target[n * kCnnOut + c];
+      dys[c] = 2.f * d / (float)(kCnnOut * N);
+      dy_out[n * kCnnOut + c] = dys[c];
+    }
+  }
+  __syncthreads();
+  if (target) {
+    if (c == 0) {
+      float l = 0.f;
+      for (int j = 0; j < kCnnOut; ++j) {
+        const float d = y_out[n * kCnnOut + j] - target[n * kCnnOut + j];
+        l += d * d;
+      }
+      lossp[n] = l;
+    }
+    if (c < Cf) {
+      float g = 0.f;
+      for (int j = 0; j < kCnnOut; ++j) g += wh[j * Cf + c] * dys[j];
+      g /= (float)npos;
+      for (long p = 0; p < npos; ++p) ga[((long)n * npos + p) * Cf + c] = g;
+    }
+  }
+}
+
+// Head gradients (single workgroup): gwh = dy^T feat, gbh = sum dy, loss = mean.
+__global__ __launch_bounds__(256) void k_head_grads(const float* __restrict__ dy,
+                                                    const float* __restrict__ feat,
+                                                    const float* __restrict__ lossp, int N, int Cf,
+                                                    float* __restrict__ gwh, float* __restrict__ gbh,
+                                                    float* __restrict__ loss) {
+  for (int i = threadIdx.x; i < kCnnOut * Cf; i += blockDim.x) {
+    const int j = i / Cf, c = i - j * Cf;
+    float s = 0.f;
+    for (int n = 0; n < N; ++n) s += dy[n * kCnnOut + j] * feat[(long)n * Cf + c];
+    gwh[i] = s;
+  }
+  if (threadIdx.x < kCnnOut) {
+    float s = 0.f;
+    for (int n = 0; n < N; ++n) s += dy[n * kCnnOut + threadIdx.x];
+    gbh[threadIdx.x] = s;
+  }
+  if (threadIdx.x == 0 && loss) {
+    float s = 0.f;
+    for (int n = 0; n < N; ++n) s += lossp[n];
+    *loss = s / (float)(N * kCnnOut);
+  }
+}
+
+// AdamW on the flat FP32 parameters; refreshes the BF16 copy of conv weights.
+__global__ void k_adamw(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
+                        float* __restrict__ v, long n, float lr, float wd, float c1, float c2,
+                        u16* __restrict__ pbf) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.f - b1) * gi;
+  const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  const float upd = (mi / c1) / (sqrtf(vi / c2) + eps) + wd * p[i];
+  const float np = p[i] - lr * upd;
+  p[i] = np;
+  pbf[i] = f2bf(np);
+}
+
+__global__ void k_to_bf16(const float* __restrict__ p, long n, u16* __restrict__ out) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = f2bf(p[i]);
+}
+
+static inline unsigned blocks(long n, int t) { return (unsigned)((n + t - 1) / t); }
+
+// ------------------------------------------------------------------ network plan
+
+struct Layer {
+  ConvGeom g;
+  int Cin, Cout;
+  long P_in, P_out;   // positions (batch included)
+  long w_off, b_off;  // offsets into the flat parameters
+};
+
+struct Net {
+  int N;
+  Layer L[kCnnLayers];
+  long wh_off, bh_off, nparam;
+  long npos_last;
+};
+
+static Net make_net(int N, int Z, int Y, int X) {
+  Net net;
+  net.N = N;
+  int D = Z, H = Y, W = X;
+  long off = 0;
+  for (int l = 0; l < kCnnLayers; ++l) {
+    Layer& L = net.L[l];
+    L.Cin = kCnnChannels[l];
+    L.Cout = kCnnChannels[l + 1];
+    L.g.D = D; L.g.H = H; L.g.W = W; L.g.C = L.Cin;
+    L.g.Do = (D - 1) / 2 + 1; L.g.Ho = (H - 1) / 2 + 1; L.g.Wo = (W - 1) / 2 + 1;
+    L.P_in = (long)N * D * H * W;
+    L.P_out = (long)N * L.g.Do * L.g.Ho * L.g.Wo;
+    L.w_off = off;
+    off += (long)L.Cout * 27 * L.Cin;
+    L.b_off = off;
+    off += L.Cout;
+    D = L.g.Do; H = L.g.Ho; W = L.g.Wo;
+  }
+  net.wh_off = off;
+  off += (long)kCnnOut * kCnnChannels[kCnnLayers];
+  net.bh_off = off;
+  off += kCnnOut;
+  net.nparam = off;
+  net.npos_last = (long)D * H * W;
+  return net;
+}
+
+long cnn_param_count() { return make_net(1, 32, 64, 64).nparam; }
+
+// Workspace for a batch: BF16 input and activations, FP32 pre-activations and
+// GEMM outputs, BF16 gradients, split-K partials, head buffers, BF16 weights.
+struct CnnWs {
+  size_t x, a[kCnnLayers], z[kCnnLayers], c, gz, ga, part, pbf, grad, head, total;
+};
+
+static size_t al(size_t x) { return (x + 255) / 256 * 256; }
+constexpr int kWgradSplitsMax = 1024;
+
+// Split-K count of a weight gradient over P output positions (>= 256 positions per split).
+static int wgrad_splits(long P) { return (int)std::min<long>(kWgradSplitsMax, std::max<long>(1, P / 256)); }
+
+static CnnWs cnn_ws(const Net& net) {
+  CnnWs w;
+  size_t b = 0;
+  auto take = [&](size_t bytes) { size_t o = b; b += al(bytes); return o; };
+  w.x = take(net.L[0].P_in * sizeof(u16));
+  long maxc = 0, maxg = 0, maxpart = 0;
+  for (int l = 0; l < kCnnLayers; ++l) {
+    const Layer& L = net.L[l];
+    w.a[l] = take(L.P_out * L.Cout * sizeof(u16));
+    w.z[l] = take(L.P_out * L.Cout * sizeof(float));
+    maxc = std::max(maxc, std::max(L.P_out * L.Cout, L.P_in * L.Cin));
+    maxg = std::max(maxg, L.P_out * L.Cout);
+    maxpart = std::max(maxpart, (long)splits_used(L.P_out, wgrad_splits(L.P_out)) * L.Cout * 27 * L.Cin);
+  }
+  w.c = take(maxc * sizeof(float));
+  w.gz = take(maxg * sizeof(u16));
+  w.ga = take(maxc * sizeof(float));
+  w.part = take(maxpart * sizeof(float));
+  w.pbf = take(net.nparam * sizeof(u16));
+  w.grad = take(net.nparam * sizeof(float));
+  w.head = take((size_t)net.N * (kCnnOut * 3 + kCnnChannels[kCnnLayers] + 2) * sizeof(float));
+  w.total = b;
+  return w;
+}
+
+size_t cnn_workspace_size(int N, int Z, int Y, int X) { return cnn_ws(make_net(N, Z, Y, X)).total; }
+
+// Forward through the convolutions (and, with targets, the backward pass that
+// fills the flat FP32 gradient).  params: FP32 flat; the BF16 copy of the
+// weights is refreshed from it at the start.
+int cnn_run(const float* params, const float* x, int N, int Z, int Y, int X, const float* target,
+            float* y_out, float* loss_out, float* grad_out, void* ws, hipStream_t s) {
+  const Net net = make_net(N, Z, Y, X);
+  const CnnWs W = cnn_ws(net);
+  char* w = (char*)ws;
+  u16* xb = (u16*)(w + W.x);
+  float* C = (float*)(w + W.c);
+  u16* gz = (u16*)(w + W.gz);
+  float* ga = (float*)(w + W.ga);
+  float* part = (float*)(w + W.part);
+  u16* pbf = (u16*)(w + W.pbf);
+  float* grad = grad_out ? grad_out : (float*)(w + W.grad);
+  float* head = (float*)(w + W.head);
+  float* dy = head;
+  float* lossp = dy + (long)N * kCnnOut;
+  float* feat = lossp + N;
+  const int Cf = kCnnChannels[kCnnLayers];
+  hipLaunchKernelGGL(k_to_bf16, dim3(blocks(net.nparam, 256)), dim3(256), 0, s, params, net.nparam, pbf);
+  hipLaunchKernelGGL(k_normalise, dim3(N), dim3(256), 0, s, x, (long)Z * Y * X, xb);
+  WO_HIP_CHECK(hipGetLastError());
+  const u16* a_in = xb;
+  for (int l = 0; l < kCnnLayers; ++l) {
+    const Layer& L = net.L[l];
+    const long K = 27L * L.Cin;
+    WO_HIP_CHECK(gemm(GatherIm2col{a_in, L.g}, GatherRows{pbf + L.w_off, K, L.Cin}, C, L.P_out, L.Cout,
+                      K, 1, s, "k_gemm_conv_fwd"));
+    float* z = (float*)(w + W.z[l]);
+    u16* a = (u16*)(w + W.a[l]);
+    hipLaunchKernelGGL(k_bias_gelu, dim3(blocks(L.P_out * L.Cout, 256)), dim3(256), 0, s, C,
+                       params + L.b_off, L.P_out, L.Cout, z, a);
+    a_in = a;
+  }
+  hipLaunchKernelGGL(k_head, dim3(N), dim3(256), 0, s, a_in, net.npos_last, Cf, params + net.wh_off,
+                     params + net.bh_off, target, N, y_out, feat, dy, lossp, ga);
+  WO_HIP_CHECK(hipGetLastError());
+  if (!target) return WO_OK;
+  hipLaunchKernelGGL(k_head_grads, dim3(1), dim3(256), 0, s, dy, feat, lossp, N, Cf,
+                     grad + net.wh_off, grad + net.bh_off, loss_out);
+  for (int l = kCnnLayers - 1; l >= 0; --l) {
+    const Layer& L = net.L[l];
+    const long K = 27L * L.Cin;
+    const float* z = (const float*)(w + W.z[l]);
+    hipLaunchKernelGGL(k_gelu_bwd, dim3(blocks(L.P_out * L.Cout, 256)), dim3(256), 0, s, ga, z,
+                       L.P_out * L.Cout, gz);
+    hipLaunchKernelGGL(k_bias_grad, dim3(L.Cout), dim3(256), 0, s, gz, L.P_out, L.Cout,
+                       grad + L.b_off);
+    const u16* a_prev = l == 0 ? xb : (const u16*)(w + W.a[l - 1]);
+    // weight gradient, split over output positions
+    const int splits = wgrad_splits(L.P_out);
+    const int zs = splits_used(L.P_out, splits);
+    WO_HIP_CHECK(gemm(GatherT{gz, L.Cout}, GatherIm2colT{GatherIm2col{a_prev, L.g}}, part, L.Cout, K,
+                      L.P_out, splits, s, "k_gemm_conv_wgrad"));
+    hipLaunchKernelGGL(k_sum_splits, dim3(blocks((long)L.Cout * K, 256)), dim3(256), 0, s, part, zs,
+                       (long)L.Cout * K, grad + L.w_off);
+    if (l > 0) {
+      ConvGeom gd = L.g;
+      gd.C = L.Cout;
+      WO_HIP_CHECK(dgrad_classes(gz, pbf + L.w_off, gd, L.Cin, net.N, ga, s));
+    }
+  }
+  return WO_OK;
+}
+
+// AdamW step on the flat parameters (t >= 1).
+hipError_t cnn_adamw(float* p, const float* g, float* m, float* v, long n, int t, float lr, float wd,
+                     void* ws_pbf, hipStream_t s) {
+  const float c1 = 1.f - powf(0.9f, (float)t), c2 = 1.f - powf(0.999f, (float)t);
+  hipLaunchKernelGGL(k_adamw, dim3(blocks(n, 256)), dim3(256), 0, s, p, g, m, v, n, lr, wd, c1, c2,
+                     (u16*)ws_pbf);
+  return hipGetLastError();
+}
+
+size_t cnn_pbf_offset(int N, int Z, int Y, int X) { return cnn_ws(make_net(N, Z, Y, X)).pbf; }
+size_t cnn_grad_offset(int N, int Z, int Y, int X) { return cnn_ws(make_net(N, Z, Y, X)).grad; }
+
+// Single convolution GEMMs for parity tests.
+hipError_t conv_fwd_raw(const u16* x, const u16* w, int N, int D, int H, int W, int Cin, int Cout,
+                        float* out, hipStream_t s) {
+  ConvGeom g{D, H, W, Cin, (D - 1) / 2 + 1, (H - 1) / 2 + 1, (W - 1) / 2 + 1};
+  const long P = (long)N * g.Do * g.Ho * g.Wo;
+  return gemm(GatherIm2col{x, g}, GatherRows{w, 27L * Cin, Cin}, out, P, Cout, 27L * Cin, 1, s,
+              "k_gemm_conv_fwd");
+}
+
+hipError_t conv_dgrad_raw(const u16* gz, const u16* w, int N, int D, int H, int W, int Cin, int Cout,
+                          float* out, hipStream_t s) {
+  ConvGeom g{D, H, W, Cout, (D - 1) / 2 + 1, (H - 1) / 2 + 1, (W - 1) / 2 + 1};
+  return dgrad_classes(gz, w, g, Cin, N, out, s);
+}
+
+hipError_t conv_wgrad_raw(const u16* x, const u16* gz, int N, int D, int H, int W, int Cin, int Cout,
+                          float* out, float* part, long part_elems, hipStream_t s) {
+  ConvGeom g{D, H, W, Cin, (D - 1) / 2 + 1, (H - 1) / 2 + 1, (W - 1) / 2 + 1};
+  const long P = (long)N * g.Do * g.Ho * g.Wo;
+  const long K = 27L * Cin;
+  int splits = wgrad_splits(P);
+  while (splits > 1 && (long)splits_used(P, splits) * Cout * K > part_elems) splits /= 2;
+  const int zs = splits_used(P, splits);
+  if ((long)zs * Cout * K > part_elems) return hipErrorInvalidValue;
+  hipError_t e = gemm(GatherT{gz, Cout}, GatherIm2colT{GatherIm2col{x, g}}, part, Cout, K, P, splits,
+                      s, "k_gemm_conv_wgrad");
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_sum_splits, dim3(blocks((long)Cout * K, 256)), dim3(256), 0, s, part, zs,
+                     (long)Cout * K, out);
+  return hipGetLastError();
+}
+
+}  // namespace wo
+
+// ------------------------------------------------------------------ training-data generators
+
+namespace wo {
+
+// SplitMix64 finaliser: a counter-based hash giving independent 64-bit words.
+__device__ __forceinline__ unsigned long long mix64(unsigned long long z) {
+  z += 0x9e3779b97f4a7c15ull;
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+  return z ^ (z >> 31);
+}
+__device__ __forceinline__ double u01(unsigned long long h) {  // (0, 1)
+  return ((double)(h >> 11) + 0.5) * (1.0 / 9007199254740992.0);
+}
+
+// Thin cells: per patch, `ncells` randomly oriented ellipses (semi-axes
+// U(0.8, 2.5) um, phase U(0.1, 0.5) rad, absorption U(0, 0.02)) with a dome
+// profile 1 - rho^2 / 2, wrapping at the tile edges; out [n][2][Y][X].
+__global__ void k_synth_cells(float* __restrict__ out, int Y, int X, double pixel, int ncells,
+                              unsigned long long seed) {
+  const long n = blockIdx.y;
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (long)Y * X) return;
+  const int y = (int)(idx / X), x = (int)(idx - (long)y * X);
+  const double Ly = Y * pixel, Lx = X * pixel;
+  double ph = 0.0, ab = 0.0;
+  for (int c = 0; c < ncells; ++c) {
+    const unsigned long long base = seed * 0x100000001b3ull + ((unsigned long long)n << 20) + (unsigned long long)c * 16;
+    const double cy = u01(mix64(base + 0)) * Ly, cx = u01(mix64(base + 1)) * Lx;
+    const double a = 0.8 + 1.7 * u01(mix64(base + 2)), b = 0.8 + 1.7 * u01(mix64(base + 3));
+    const double t = M_PI * u01(mix64(base + 4));
+    const double p0 = 0.1 + 0.4 * u01(mix64(base + 5)), a0 = 0.02 * u01(mix64(base + 6));
+    double dy = y * pixel - cy + 0.5 * Ly, dx = x * pixel - cx + 0.5 * Lx;
+    dy = dy - floor(dy / Ly) * Ly - 0.5 * Ly;
+    dx = dx - floor(dx / Lx) * Lx - 0.5 * Lx;
+    const double u = dx * cos(t) + dy * sin(t), v = -dx * sin(t) + dy * cos(t);
+    const double r2 = (u / a) * (u / a) + (v / b) * (v / b);
+    if (r2 <= 1.0) {
+      ph += p0 * (1.0 - 0.5 * r2);
+      ab += a0 * (1.0 - 0.5 * r2);
+    }
+  }
+  out[(n * 2 + 0) * (long)Y * X + idx] = (float)ph;
+  out[(n * 2 + 1) * (long)Y * X + idx] = (float)ab;
+}
+
+// x += sigma * N(0, 1) (Box-Muller on hashed counters)
+__global__ void k_add_noise(float* __restrict__ x, long n, float sigma, unsigned long long seed) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const unsigned long long h1 = mix64(seed ^ (2ull * (unsigned long long)i));
+  const unsigned long long h2 = mix64(seed ^ (2ull * (unsigned long long)i + 1ull));
+  const double r = sqrt(-2.0 * log(u01(h1)));
+  x[i] += sigma * (float)(r * cos(2.0 * M_PI * u01(h2)));
+}
+
+}  // namespace wo
+
+// ------------------------------------------------------------------ C ABI
+
+extern "C" {
+
+int64_t wo_cnn_param_count(void) { return wo::cnn_param_count(); }
+
+int wo_synth_thin_cells(float* out, int32_t n, int32_t ny, int32_t nx, double pixel, int32_t ncells,
+                        uint64_t seed, void* stream) {
+  if (!out || n < 1 || n > 65535 || ny < 1 || nx < 1 || !(pixel > 0) || ncells < 0) return WO_EINVAL;
+  dim3 grid(wo::blocks((long)ny * nx, 256), n);
+  hipLaunchKernelGGL(wo::k_synth_cells, grid, dim3(256), 0, (hipStream_t)stream, out, ny, nx, pixel,
+                     ncells, (unsigned long long)seed);
+  WO_HIP_CHECK(hipGetLastError());
+  return WO_OK;
+}
+
+int wo_add_gaussian_noise(float* x, int64_t n, double sigma, uint64_t seed, void* stream) {
+  if (!x || n < 0) return WO_EINVAL;
+  if (n == 0) return WO_OK;
+  hipLaunchKernelGGL(wo::k_add_noise, dim3(wo::blocks(n, 256)), dim3(256), 0, (hipStream_t)stream, x,
+                     (long)n, (float)sigma, (unsigned long long)seed);
+  WO_HIP_CHECK(hipGetLastError());
+  return WO_OK;
+}
+
+static bool cnn_shape_ok(int32_t batch, int32_t nz, int32_t ny, int32_t nx) {
+  return batch >= 1 && batch <= 65535 && nz >= 1 && ny >= 1 && nx >= 1 && nz <= 1024 && ny <= 4096 &&
+         nx <= 4096;
+}
+
+size_t wo_cnn_workspace_size(int32_t batch, int32_t nz, int32_t ny, int32_t nx) {
+  if (!cnn_shape_ok(batch, nz, ny, nx)) return 0;
+  return wo::cnn_workspace_size(batch, nz, ny, nx);
+}
+
+int wo_cnn_forward(const float* params, const float* x, int32_t batch, int32_t nz, int32_t ny,
+                   int32_t nx, float* y_out, void* ws, size_t ws_bytes, void* stream) {
+  if (!params || !x || !y_out || !ws || !cnn_shape_ok(batch, nz, ny, nx)) return WO_EINVAL;
+  if (ws_bytes < wo::cnn_workspace_size(batch, nz, ny, nx)) return WO_ENOMEM;
+  return wo::cnn_run(params, x, batch, nz, ny, nx, nullptr, y_out, nullptr, nullptr, ws,
+                     (hipStream_t)stream);
+}
+
+int wo_cnn_gradient(const float* params, const float* x, const float* target, int32_t batch,
+                    int32_t nz, int32_t ny, int32_t nx, float* y_out, float* loss_out,
+                    float* grad_out, void* ws, size_t ws_bytes, void* stream) {
+  if (!params || !x || !target || !y_out || !ws || !cnn_shape_ok(batch, nz, ny, nx)) return WO_EINVAL;
+  if (ws_bytes < wo::cnn_workspace_size(batch, nz, ny, nx)) return WO_ENOMEM;
+  return wo::cnn_run(params, x, batch, nz, ny, nx, target, y_out, loss_out, grad_out, ws,
+                     (hipStream_t)stream);
+}
+
+int wo_cnn_train_step(float* params, float* adam_m, float* adam_v, int32_t t, double lr,
+                      double weight_decay, const float* x, const float* target, int32_t batch,
+                      int32_t nz, int32_t ny, int32_t nx, float* y_out, float* loss_out, void* ws,
+                      size_t ws_bytes, void* stream) {
+  if (!params || !adam_m || !adam_v || t < 1 || !(lr >= 0) || !(weight_decay >= 0)) return WO_EINVAL;
+  int st = wo_cnn_gradient(params, x, target, batch, nz, ny, nx, y_out, loss_out, nullptr, ws,
+                           ws_bytes, stream);
+  if (st) return st;
+  char* w = (char*)ws;
+  const float* g = (const float*)(w + wo::cnn_grad_offset(batch, nz, ny, nx));
+  void* pbf = w + wo::cnn_pbf_offset(batch, nz, ny, nx);
+  WO_HIP_CHECK(wo::cnn_adamw(params, g, adam_m, adam_v, wo::cnn_param_count(), t, (float)lr,
+                             (float)weight_decay, pbf, (hipStream_t)stream));
+  return WO_OK;
+}
+
+static bool conv_ok(int N, int D, int H, int W, int Cin, int Cout) {
+  return N >= 1 && D >= 1 && H >= 1 && W >= 1 && Cin >= 1 && Cout >= 1 && Cin <= 4096 &&
+         Cout <= 4096;
+}
+
+int wo_conv3d_forward(const uint16_t* x, const uint16_t* w, int32_t N, int32_t D, int32_t H,
+                      int32_t W, int32_t Cin, int32_t Cout, float* out, void* stream) {
+  if (!x || !w || !out || !conv_ok(N, D, H, W, Cin, Cout)) return WO_EINVAL;
+  WO_HIP_CHECK(wo::conv_fwd_raw(x, w, N, D, H, W, Cin, Cout, out, (hipStream_t)stream));
+  return WO_OK;
+}
+
+int wo_conv3d_input_grad(const uint16_t* gz, const uint16_t* w, int32_t N, int32_t D, int32_t H,
+                         int32_t W, int32_t Cin, int32_t Cout, float* out, void* stream) {
+  if (!gz || !w || !out || !conv_ok(N, D, H, W, Cin, Cout)) return WO_EINVAL;
+  WO_HIP_CHECK(wo::conv_dgrad_raw(gz, w, N, D, H, W, Cin, Cout, out, (hipStream_t)stream));
+  return WO_OK;
+}
+
+int wo_conv3d_weight_grad(const uint16_t* x, const uint16_t* gz, int32_t N, int32_t D, int32_t H,
+                          int32_t W, int32_t Cin, int32_t Cout, float* out, void* ws,
+                          size_t ws_bytes, void* stream) {
+  if (!x || !gz || !out || !ws || !conv_ok(N, D, H, W, Cin, Cout)) return WO_EINVAL;
+  WO_HIP_CHECK(wo::conv_wgrad_raw(x, gz, N, D, H, W, Cin, Cout, out, (float*)ws,
+                                  (long)(ws_bytes / sizeof(float)), (hipStream_t)stream));
+  return WO_OK;
+}
+
+}  // extern "C"

@@ -8,6 +8,17 @@
 
 namespace wo {
 
+#define WO_HIP_CHECK(expr)                  \
+  do {                                      \
+    hipError_t _e = (expr);                 \
+    if (_e != hipSuccess) return WO_EHIP;   \
+  } while (0)
+
+// Parameter-regression CNN: channels of the 4 convolution blocks and outputs.
+constexpr int kCnnLayers = 4;
+constexpr int kCnnOut = 3;
+constexpr int kCnnChannels[kCnnLayers + 1] = {1, 32, 64, 128, 256};
+
 // Dynamic LDS bytes one workgroup may use on the current device (queried once).
 long lds_limit_bytes();
 

@@ -1,0 +1,130 @@
+"""BF16-MFMA CNN kernels vs the FP64 oracle (learned initialiser of the auto-tune).
+
+Single convolutions get identical BF16 operands on both sides, so the only
+difference is FP32 vs FP64 accumulation: relative L2 <= 1e-5.  The whole
+network (forward + backward) is compared with the oracle emulating the same
+BF16 roundings: loss relative error <= 1e-3, gradient relative L2 <= 1e-2.
+"""
+
+import numpy as np
+import pytest
+
+from oracle import cnn
+
+pytestmark = pytest.mark.gpu
+
+
+def to_bits(a):
+    """float64 array already on the BF16 grid -> int16 bit patterns."""
+    u = np.asarray(a, dtype=np.float32).view(np.uint32) >> 16
+    return u.astype(np.uint16).view(np.int16)
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a, np.float64) - b) / np.linalg.norm(b))
+
+
+SHAPES = [(2, 8, 12, 10, 8, 40), (1, 9, 7, 6, 1, 32), (2, 16, 32, 32, 32, 64)]
+
+
+@pytest.mark.parametrize("N,D,H,W,Ci,Co", SHAPES)
+def test_conv_kernels_match_oracle(gpu_lib, N, D, H, W, Ci, Co):
+    import torch
+    print(f"[case] conv N={N} D={D} H={H} W={W} Cin={Ci} Cout={Co}", flush=True)
+    rng = np.random.default_rng(N * 1000 + Ci)
+    x = cnn.bf16(rng.standard_normal((N, D, H, W, Ci)))
+    w = cnn.bf16(rng.standard_normal((Co, 3, 3, 3, Ci)) / np.sqrt(27 * Ci))
+    xb = torch.from_numpy(to_bits(x)).cuda()
+    wb = torch.from_numpy(to_bits(w.reshape(Co, -1))).cuda()
+    z = gpu_lib.conv3d_forward(xb, wb, Co).cpu().numpy()
+    ref = cnn.conv3d(x, w)
+    e = rel(z, ref)
+    print(f"  forward rel {e:.2e}")
+    assert e < 1e-5
+    gz = cnn.bf16(rng.standard_normal(ref.shape))
+    gzb = torch.from_numpy(to_bits(gz)).cuda()
+    gx = gpu_lib.conv3d_input_grad(gzb, wb, x.shape).cpu().numpy()
+    e = rel(gx, cnn.conv3d_dgrad(gz, w, x.shape))
+    print(f"  input grad rel {e:.2e}")
+    assert e < 1e-5
+    gw = gpu_lib.conv3d_weight_grad(xb, gzb).cpu().numpy()
+    gw_ref, _ = cnn.conv3d_wgrad(x, gz)
+    e = rel(gw, gw_ref.reshape(Co, -1))
+    print(f"  weight grad rel {e:.2e}")
+    assert e < 1e-5
+
+
+def test_network_gradient_matches_oracle(gpu_lib):
+    import torch
+    from paper_2412_09775_amd import learned_init
+    rng = np.random.default_rng(9)
+    p = learned_init.init_params(5)
+    p[-3:] = [0.1, -0.2, 0.05]                    # non-zero head bias
+    stacks = rng.standard_normal((2, 8, 16, 16)).astype(np.float32)
+    target = rng.uniform(-1, 1, (2, 3)).astype(np.float32)
+    y, loss, g = gpu_lib.cnn_gradient(torch.from_numpy(p).cuda(), torch.from_numpy(stacks).cuda(),
+                                      torch.from_numpy(target).cuda())
+    x = cnn.normalise_input(stacks)
+    L, gref = cnn.loss_and_grad(p.astype(np.float64), x, target.astype(np.float64), round_bf16=True)
+    yref, _ = cnn.forward(p.astype(np.float64), x, round_bf16=True)
+    print(f"  loss {float(loss):.6f} vs {L:.6f}; y rel {rel(y.cpu().numpy(), yref):.2e}; "
+          f"grad rel {rel(g.cpu().numpy(), gref):.2e}")
+    assert abs(float(loss) - L) <= 1e-3 * abs(L)
+    assert rel(y.cpu().numpy(), yref) < 1e-3
+    assert rel(g.cpu().numpy(), gref) < 1e-2
+    # per-layer gradient blocks, so no layer hides behind the norm of another
+    off = 0
+    for kind, shp in cnn.param_shapes():
+        n = int(np.prod(shp))
+        e = rel(g.cpu().numpy()[off:off + n], gref[off:off + n]) if np.any(gref[off:off + n]) else 0.0
+        assert e < 2e-2, (kind, shp, e)
+        off += n
+
+
+def test_adamw_step_matches_oracle(gpu_lib):
+    import torch
+    from paper_2412_09775_amd import learned_init
+    n = gpu_lib.cnn_param_count()
+    rng = np.random.default_rng(3)
+    p = learned_init.init_params(1)
+    stacks = rng.standard_normal((2, 8, 16, 16)).astype(np.float32)
+    target = rng.uniform(-1, 1, (2, 3)).astype(np.float32)
+    pt = torch.from_numpy(p).cuda()
+    m, v = torch.zeros(n, device="cuda"), torch.zeros(n, device="cuda")
+    _, _, g = gpu_lib.cnn_gradient(pt.clone(), torch.from_numpy(stacks).cuda(), torch.from_numpy(target).cuda())
+    ws = gpu_lib.cnn_workspace(2, (8, 16, 16), "cuda")
+    y = torch.empty((2, 3), device="cuda")
+    loss = torch.empty(1, device="cuda")
+    gpu_lib.cnn_train_step(pt, m, v, 1, 1e-3, 1e-4, torch.from_numpy(stacks).cuda(),
+                           torch.from_numpy(target).cuda(), ws, y, loss)
+    ref, _, _ = cnn.adamw_step(p.astype(np.float64), g.cpu().numpy().astype(np.float64), np.zeros(n),
+                               np.zeros(n), 1, 1e-3, 1e-4)
+    assert np.max(np.abs(pt.cpu().numpy() - ref)) < 1e-6
+
+
+def test_training_data_is_deterministic(gpu_lib):
+    a = gpu_lib.synth_thin_cells(3, 64, 64, 0.1, 8, 42).cpu().numpy()
+    b = gpu_lib.synth_thin_cells(3, 64, 64, 0.1, 8, 42).cpu().numpy()
+    c = gpu_lib.synth_thin_cells(3, 64, 64, 0.1, 8, 43).cpu().numpy()
+    assert np.array_equal(a, b) and not np.array_equal(a, c)
+    assert 0.0 <= a[:, 0].min() and a[:, 0].max() < 8 * 0.5 and a[:, 1].max() < 8 * 0.02
+    import torch
+    x = torch.zeros(1 << 20, device="cuda")
+    gpu_lib.add_gaussian_noise(x, 0.5, 7)
+    s = x.cpu().numpy()
+    assert abs(s.mean()) < 2e-3 and abs(s.std() - 0.5) < 2e-3
+
+
+def test_training_reduces_the_loss(gpu_lib):
+    import torch
+    from paper_2412_09775_amd import learned_init
+    # 64x64 patches: a quarter-pixel soft edge has the same absolute width as
+    # half a pixel on 128x128 tiles and keeps NA 1.3 inside the shell
+    tmpl = gpu_lib.Optics(model=2, nz=32, ny=64, nx=64, dz=0.2, dy=0.1, dx=0.1, wavelength=0.532,
+                          na_ill=0.5, na_det=1.15, n_medium=1.33, edge_width=0.25)
+    stacks, theta = learned_init.simulate(tmpl, 1024, seed=11, device="cuda")
+    net = learned_init.LearnedInit("cuda", seed=2)
+    hist = net.train(stacks, theta, epochs=4, batch=64, lr=1e-3)
+    torch.cuda.synchronize()
+    print(f"  epoch losses {hist}")
+    assert hist[-1] < 0.7 * hist[0]
