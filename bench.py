@@ -99,6 +99,9 @@ def main():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--tune-patches", type=int, default=256)
     ap.add_argument("--tune-iters", type=int, default=100)
+    ap.add_argument("--cnn-train-patches", type=int, default=16384)
+    ap.add_argument("--cnn-epochs", type=int, default=8)
+    ap.add_argument("--cnn-tune-iters", type=int, default=20)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for HBM counters)")
     args = ap.parse_args()
@@ -215,7 +218,8 @@ def main():
     }
 
     if not args.no_autotune:
-        out["autotune"] = autotune_section(api, torch, dev, args.tune_patches, args.tune_iters)
+        out["autotune"] = autotune_section(api, torch, dev, args.tune_patches, args.tune_iters,
+                                           args.cnn_train_patches, args.cnn_epochs, args.cnn_tune_iters)
     if args.calibrate_copy:
         src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
@@ -238,11 +242,14 @@ TUNE_RANGE = np.array([4.0, 0.3, math.radians(30.0)])
 TUNE_LR = (0.02, 0.005, 0.005, 0.001)
 TUNE_LO = (-2.5, 1.0, 0.0, -1.0)
 TUNE_HI = (2.5, 1.3, math.radians(32.0), 1.0)
+# tuned parameters: defocus and illumination zenith tilt, as in the paper's auto-tune;
+# NA_det keeps its starting value (nominal, or the learned initialiser's prediction)
+TUNE_MASK = 0b0101
 
 
-def autotune_section(api, torch, dev, n, iters):
-    """Patches/s of the batched GPU auto-tune (single start and 8-start multistart)
-    and the median normalised parameter error |theta - truth| / range."""
+def autotune_section(api, torch, dev, n, iters, cnn_patches, cnn_epochs, cnn_iters):
+    """Patches/s of the batched GPU auto-tune (single start, 8-start multistart and
+    CNN-initialised) and the median normalised parameter error |theta - truth| / range."""
     import synth
     rng = np.random.default_rng(4001)
     truth = np.stack([rng.uniform(-2, 2, n), rng.uniform(1.0, 1.3, n),
@@ -264,7 +271,8 @@ def autotune_section(api, torch, dev, n, iters):
         e = np.abs(th[:, :3] - truth) / TUNE_RANGE
         return float(np.median(e.max(axis=1))), [float(x) for x in np.median(e, axis=0)]
 
-    res = {"workload": f"{n} patches 32x128x128, {iters} Adam iterations, hipGraph replay"}
+    res = {"workload": f"{n} patches 32x128x128, {iters} Adam iterations, hipGraph replay, "
+                       "tuning defocus and zenith tilt"}
     for label, M in (("single_start", 1), ("multistart_8", 8)):
         theta0 = None
         if M > 1:
@@ -276,11 +284,13 @@ def autotune_section(api, torch, dev, n, iters):
             theta0[:, :, 2] = grid[None, :, 1]
         ws = torch.empty(api.tune_workspace_size(starts, M), dtype=torch.uint8, device=dev)
         api.autotune(starts[:1], d[:1], eta, iters=2, lr=TUNE_LR, lo=TUNE_LO, hi=TUNE_HI, multistart=M,
-                     theta0=None if theta0 is None else theta0[:1], nu_c=nu_c, use_graph=True, ws=ws)
+                     theta0=None if theta0 is None else theta0[:1], nu_c=nu_c, use_graph=True, ws=ws,
+                     mask=TUNE_MASK)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         out, loss, _, _ = api.autotune(starts, d, eta, iters=iters, lr=TUNE_LR, lo=TUNE_LO, hi=TUNE_HI,
-                                       multistart=M, theta0=theta0, nu_c=nu_c, use_graph=True, ws=ws)
+                                       multistart=M, theta0=theta0, nu_c=nu_c, use_graph=True, ws=ws,
+                                       mask=TUNE_MASK)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         th = np.array([[o.defocus, o.na_det, o.tilt_zenith, o.tilt_azimuth] for o in out])
@@ -290,6 +300,51 @@ def autotune_section(api, torch, dev, n, iters):
                       "median_norm_err_defocus_na_tilt": [round(x, 4) for x in per]}
         del ws
         print(f"[bench] autotune {label}: {n / dt:.1f} patches/s, median err {med:.3f}",
+              file=sys.stderr, flush=True)
+
+    # learned initialiser: train on simulated 32x64x64 patches (not timed in patches/s),
+    # then CNN prediction + a short single-start auto-tune on the same tiles
+    if cnn_patches > 0:
+        from paper_2412_09775_amd import learned_init
+        tmpl64 = api.Optics(**dict(TUNE, ny=64, nx=64, edge_width=0.25))
+        t0 = time.perf_counter()
+        stacks, theta = learned_init.simulate(tmpl64, cnn_patches, seed=6001, device=dev)
+        torch.cuda.synchronize()
+        t_sim = time.perf_counter() - t0
+        net = learned_init.LearnedInit(dev, seed=0)
+        t0 = time.perf_counter()
+        hist = net.train(stacks, theta, epochs=cnn_epochs, batch=64, lr=1e-3)
+        torch.cuda.synchronize()
+        t_train = time.perf_counter() - t0
+        del stacks
+        print(f"[bench] cnn trained: {cnn_patches} patches x {cnn_epochs} epochs in {t_train:.1f}s, "
+              f"loss {hist[0]:.3f} -> {hist[-1]:.3f}", file=sys.stderr, flush=True)
+        ws = torch.empty(api.tune_workspace_size(starts, 1), dtype=torch.uint8, device=dev)
+        net.predict(d[:8])
+        api.autotune(starts[:1], d[:1], eta, iters=2, lr=TUNE_LR, lo=TUNE_LO, hi=TUNE_HI, nu_c=nu_c,
+                     use_graph=True, ws=ws, mask=TUNE_MASK)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        pred = net.predict(d)
+        theta0 = np.zeros((n, 1, 4))
+        theta0[:, 0, :3] = np.clip(pred, np.array(TUNE_LO[:3]), np.array(TUNE_HI[:3]))
+        out, loss, _, _ = api.autotune(starts, d, eta, iters=cnn_iters, lr=TUNE_LR, lo=TUNE_LO, hi=TUNE_HI,
+                                       theta0=theta0, nu_c=nu_c, use_graph=True, ws=ws, mask=TUNE_MASK)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        th = np.array([[o.defocus, o.na_det, o.tilt_zenith, o.tilt_azimuth] for o in out])
+        med, per = err(th)
+        med0, per0 = err(np.concatenate([pred, np.zeros((n, 1))], 1))
+        res["cnn_init"] = {"patches_per_s": n / dt, "seconds": round(dt, 3), "tune_iters": cnn_iters,
+                           "median_norm_param_err": round(med, 4),
+                           "median_norm_err_defocus_na_tilt": [round(x, 4) for x in per],
+                           "cnn_only_median_norm_err_defocus_na_tilt": [round(x, 4) for x in per0],
+                           "train": {"patches": cnn_patches, "epochs": cnn_epochs, "batch": 64,
+                                     "simulate_s": round(t_sim, 2), "train_s": round(t_train, 2),
+                                     "loss_first_last": [round(hist[0], 4), round(hist[-1], 4)]}}
+        ms = res["multistart_8"]["patches_per_s"]
+        res["cnn_init"]["speedup_vs_multistart_8"] = round(n / dt / ms, 2)
+        print(f"[bench] cnn init: {n / dt:.1f} patches/s, median err {med:.3f} (cnn only {med0:.3f})",
               file=sys.stderr, flush=True)
     return res
 
