@@ -178,3 +178,36 @@ def bank_shape(o: op.Optics):
     if o.model == op.POL5_3D:
         return 5, 4, 3
     raise ValueError(o.model)
+
+
+def labelfree_response_at(o: op.Optics, ky: int, kx: int) -> np.ndarray:
+    """C_z(nu_perp) for every plane at one lateral frequency index (ky, kx), by the
+    direct sum over source points q (Table 1, [P * PS] as a correlation):
+
+        C_z(nu) = sum_q S(q) P(q) P(q + nu) g(q + nu) e^{i 2 pi (kz(q + nu) - kz(q)) (z - dz0)} / I_bg
+
+    Independent of any FFT; used to check full-size banks frequency by frequency.
+    Returns (Z,) complex.
+    """
+    S = op.illumination_pupil(o)
+    P = op.detection_pupil(o)
+    g = op.greens_spectrum(o)
+    kzz = op.axial_wavenumber(o)
+    ibg = float(np.sum(S * P * P))
+    qy, qx = np.nonzero(S * P)
+    py, px = (qy + ky) % o.ny, (qx + kx) % o.nx        # q + nu on the periodic grid
+    w = S[qy, qx] * P[qy, qx] * P[py, px] * g[py, px]
+    dk = kzz[py, px] - kzz[qy, qx]
+    zs = _planes(o) - o.defocus
+    return np.exp(2j * np.pi * np.outer(zs, dk)) @ w / ibg
+
+
+def labelfree_3d_at(o: op.Optics, kz: int, ky: int, kx: int):
+    """(H_phase, H_abs) of the 3D label-free model at one frequency index, from
+    labelfree_response_at at nu and -nu and a direct DFT along z."""
+    cp = labelfree_response_at(o, ky, kx)
+    cm = labelfree_response_at(o, (-ky) % o.ny, (-kx) % o.nx)
+    ez = np.exp(-2j * np.pi * kz * np.arange(o.nz) / o.nz)
+    hp = np.sum(ez * (cp + np.conj(cm)))
+    ha = np.sum(ez * 1j * (cp - np.conj(cm)))
+    return hp, ha

@@ -388,3 +388,12 @@ def test_adam_first_step_is_signed_learning_rate():
 def test_hard_edges_of_test_optics_are_not_on_lattice_points():
     for o in (lf_optics(), fl_optics()):
         assert op.hard_edge_margin(o) > 1e-6
+
+
+def test_direct_frequency_sum_equals_the_bank():
+    """One-frequency evaluation by the direct source sum (no FFT) equals the FFT-route bank."""
+    o = lf_optics(nz=8, ny=32, nx=32, defocus=0.1, tilt_zenith=0.1, tilt_azimuth=0.4)
+    hp, ha = tfm.labelfree_3d(o)
+    for kz, ky, kx in [(0, 0, 0), (1, 2, 3), (7, 31, 5), (3, 10, 30), (4, 16, 16)]:
+        a, b = tfm.labelfree_3d_at(o, kz, ky, kx)
+        assert abs(a - hp[kz, ky, kx]) < 1e-12 and abs(b - ha[kz, ky, kx]) < 1e-12
