@@ -126,6 +126,7 @@ long loss_blocks(const Sampling& sm) {
 // gam: [v][Z][2][Y][X] real (Gamma phase, absorption).  Replaces field 0 by the
 // inverse X transform of u_A = conj(Gamma b)/(N I_bg) and field 1 by that of
 // u_B = Gamma conj(a)/(N I_bg); dpart[v * wpp + wg] = sum Re(Gamma b conj(a)).
+template <int NS>
 __global__ __launch_bounds__(1024) void k_tf_rows_bwd(const double* __restrict__ partials,
                                                       long tiles_x, Sampling sm,
                                                       float2* __restrict__ ab,
@@ -160,7 +161,7 @@ __global__ __launch_bounds__(1024) void k_tf_rows_bwd(const double* __restrict__
     return src[(row0 + r) * X + i];
   });
   __syncthreads();
-  lds_fft(buf, LdsLines{2 * nr, 1, X, false}, plan, tw, 1.f, tid, nthr);
+  fft_lines<NS, 0, false>(buf, LdsLines{2 * nr, 1, X, false}, plan, tw, 1.f, tid, nthr);
   const float k = (float)(1.0 / ((double)X * (double)Y * ibg_s));
   double dsum = 0.0;
   for (int e = tid; e < nr * X; e += nthr) {
@@ -179,7 +180,7 @@ __global__ __launch_bounds__(1024) void k_tf_rows_bwd(const double* __restrict__
   const double tot = block_sum_d(dsum, red);
   if (tid == 0) dpart[v * wg_per_patch + wg] = tot;
   __syncthreads();
-  lds_fft(buf, LdsLines{2 * nr, 1, X, false}, plan, tw, 1.f, tid, nthr);
+  fft_lines<NS, 0, false>(buf, LdsLines{2 * nr, 1, X, false}, plan, tw, 1.f, tid, nthr);
   scatter_from_lds(buf, nr * 2 * X, tid, nthr, [&](int e, float2 val) {
     const int i = e % X;
     const int t = e / X;
@@ -210,9 +211,20 @@ hipError_t launch_tf_rows_bwd(const double* partials, const Sampling& sm, int nv
   const long tiles_x = (sm.nx + tf_tile_width(sm) - 1) / tf_tile_width(sm);
   const int thr = threads_for(2L * R * sm.nx);
   const size_t lds = (size_t)(sm.nx + 2 * R * sm.nx) * sizeof(float2);
-  { ScopedTiming _t("k_tf_rows_bwd", s);
-  hipLaunchKernelGGL(k_tf_rows_bwd, dim3((unsigned)(wpp * nv)), dim3(thr), lds, s, partials,
-                     tiles_x, sm, ab, gam, dpart, R, wpp, plan); }
+  ScopedTiming _t("k_tf_rows_bwd", s);
+#define X_(NN)                                                                                   \
+  case NN:                                                                                       \
+    hipLaunchKernelGGL((k_tf_rows_bwd<NN>), dim3((unsigned)(wpp * nv)), dim3(thr), lds, s, partials, \
+                       tiles_x, sm, ab, gam, dpart, R, wpp, plan);                               \
+    return hipGetLastError();
+  switch (sm.nx) {
+    WO_LATERAL_SIZES(X_)
+    default:
+      break;
+  }
+#undef X_
+  hipLaunchKernelGGL((k_tf_rows_bwd<0>), dim3((unsigned)(wpp * nv)), dim3(thr), lds, s, partials,
+                     tiles_x, sm, ab, gam, dpart, R, wpp, plan);
   return hipGetLastError();
 }
 
@@ -221,6 +233,7 @@ hipError_t launch_tf_rows_bwd(const double* partials, const Sampling& sm, int nv
 // Inverse Y transform of u_A, u_B columns, then per lateral frequency the
 // contraction 4 Re(U_B dB/dtheta + U_A dA/dtheta).  gpart[((v*Z + z)*tiles + tile)*4 + j];
 // plane-0 workgroups also write dI_bg/dtheta partials to ipart[(v*tiles + tile)*4 + j].
+template <int NS>
 __global__ __launch_bounds__(1024) void k_tf_grad_y(const DevOptics* __restrict__ opt, Sampling sm,
                                                     const float2* __restrict__ ab,
                                                     double* __restrict__ gpart,
@@ -247,7 +260,7 @@ __global__ __launch_bounds__(1024) void k_tf_grad_y(const DevOptics* __restrict_
     return kx < X ? ab[(((v * 2 + f) * Z + z) * (long)Y + ky) * X + kx] : make_float2(0.f, 0.f);
   });
   __syncthreads();
-  lds_fft(buf, LdsLines{2 * W, 2 * W, 1, true}, plan, tw, 1.f, tid, nthr);
+  fft_lines<NS, 0, true>(buf, LdsLines{2 * W, 2 * W, 1, true}, plan, tw, 1.f, tid, nthr);
   const double hw = soft_halfwidth(o, sm);
   const double km = o.n_medium / o.wavelength;
   const double rd = o.na_det / o.wavelength, ri = o.na_ill / o.wavelength;
@@ -326,9 +339,20 @@ hipError_t launch_tf_grad_y(const DevOptics* opt, const Sampling& sm, int nv, co
   const long nwg = tiles * sm.nz * (long)nv;
   const int thr = threads_for((long)sm.ny * 2 * W);
   const size_t lds = (size_t)(sm.ny + sm.ny * 2 * W) * sizeof(float2);
-  { ScopedTiming _t("k_tf_grad_y", s);
-  hipLaunchKernelGGL(k_tf_grad_y, dim3((unsigned)nwg), dim3(thr), lds, s, opt, sm, ab, gpart, ipart,
-                     W, tiles, plan); }
+  ScopedTiming _t("k_tf_grad_y", s);
+#define X_(NN)                                                                                   \
+  case NN:                                                                                       \
+    hipLaunchKernelGGL((k_tf_grad_y<NN>), dim3((unsigned)nwg), dim3(thr), lds, s, opt, sm, ab, gpart, \
+                       ipart, W, tiles, plan);                                                   \
+    return hipGetLastError();
+  switch (sm.ny) {
+    WO_LATERAL_SIZES(X_)
+    default:
+      break;
+  }
+#undef X_
+  hipLaunchKernelGGL((k_tf_grad_y<0>), dim3((unsigned)nwg), dim3(thr), lds, s, opt, sm, ab, gpart, ipart,
+                     W, tiles, plan);
   return hipGetLastError();
 }
 

@@ -182,6 +182,25 @@ __device__ __forceinline__ void gather_to_lds(float2* buf, int total, int tid, i
   }
 }
 
+// As above, running mid() after the loads are issued and before the LDS stores
+// (e.g. to generate twiddles while the loads are in flight).
+template <typename F, typename G>
+__device__ __forceinline__ void gather_to_lds(float2* buf, int total, int tid, int nthr, F src,
+                                              G mid) {
+  float2 t[kEmax];
+#pragma unroll
+  for (int i = 0; i < kEmax; ++i) {
+    const int e = tid + i * nthr;
+    if (e < total) t[i] = src(e);
+  }
+  mid();
+#pragma unroll
+  for (int i = 0; i < kEmax; ++i) {
+    const int e = tid + i * nthr;
+    if (e < total) buf[e] = t[i];
+  }
+}
+
 // Cooperative write-out of `total` (<= kEmax * nthr) elements: dst(e, value).
 template <typename F>
 __device__ __forceinline__ void scatter_from_lds(const float2* buf, int total, int tid, int nthr,
@@ -355,3 +374,113 @@ __device__ __forceinline__ double plane_z(int k, const Sampling& sm) {
 }
 
 }  // namespace wo
+
+namespace wo {
+
+// ---------------------------------------------------------------- static-length FFT
+//
+// The same Stockham passes with the length, radices, spans and (optionally)
+// the line count fixed at compile time, so index arithmetic becomes constants
+// and shifts.  Used for the transform lengths of the workloads; other lengths
+// take the runtime plan above.
+
+template <int N>
+struct StaticPlan {
+  static constexpr int radix(int q) {
+    int m = N, p = 0;
+    const int order[5] = {8, 4, 2, 3, 5};
+    for (int i = 0; i < 5; ++i) {
+      const int f = order[i];
+      while (m % f == 0) {
+        if (p == q) return f;
+        m /= f;
+        ++p;
+      }
+    }
+    return 0;
+  }
+  static constexpr int passes() {
+    int p = 0;
+    while (radix(p)) ++p;
+    return p;
+  }
+  static constexpr int span(int q) {
+    int s = 1;
+    for (int i = 0; i < q; ++i) s *= radix(i);
+    return s;
+  }
+};
+
+template <int N, int R, int NS, int NL, bool LF>
+__device__ __forceinline__ void static_pass(float2* lds, int nl_rt, int es, int ls, const float2* tw,
+                                            float s, int tid, int nthr) {
+  constexpr int NB = N / R;
+  constexpr int BPT = (kEmax + R - 1) / R;
+  constexpr int TWS = N / (NS * R);
+  const int nl = NL > 0 ? NL : nl_rt;
+  const int total = nl * NB;
+  float2 v[BPT][R];
+  int base[BPT], kk[BPT];
+#pragma unroll
+  for (int b = 0; b < BPT; ++b) {
+    const int j = tid + b * nthr;
+    base[b] = -1;
+    if (j < total) {
+      int l, k;
+      if (LF) { l = j % nl; k = j / nl; }
+      else { k = j % NB; l = j / NB; }
+      const int lb = l * ls;
+      const int km = k % NS;
+      base[b] = lb;
+      kk[b] = k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        float2 x = lds[lb + (k + r * NB) * es];
+        if (r > 0) {
+          float2 w = tw[r * km * TWS];
+          if (s > 0.f) w.y = -w.y;
+          x = cmul(x, w);
+        }
+        v[b][r] = x;
+      }
+      dft_small<R>(v[b], s);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int b = 0; b < BPT; ++b) {
+    if (base[b] >= 0) {
+      const int k = kk[b];
+      const int d0 = (k / NS) * NS * R + (k % NS);
+#pragma unroll
+      for (int r = 0; r < R; ++r) lds[base[b] + (d0 + r * NS) * es] = v[b][r];
+    }
+  }
+  __syncthreads();
+}
+
+template <int N, int NL, bool LF, int Q = 0>
+__device__ __forceinline__ void static_fft(float2* lds, int nl_rt, int es, int ls, const float2* tw,
+                                           float s, int tid, int nthr) {
+  if constexpr (Q < StaticPlan<N>::passes()) {
+    static_pass<N, StaticPlan<N>::radix(Q), StaticPlan<N>::span(Q), NL, LF>(lds, nl_rt, es, ls, tw, s,
+                                                                            tid, nthr);
+    static_fft<N, NL, LF, Q + 1>(lds, nl_rt, es, ls, tw, s, tid, nthr);
+  }
+}
+
+// FFT of the lines described by L: static length NSTAT (> 0) or the runtime plan
+// (NSTAT == 0).  NL > 0 fixes the number of lines; LF must equal L.linefast.
+template <int NSTAT, int NL, bool LF>
+__device__ __forceinline__ void fft_lines(float2* lds, const LdsLines& L, const FftPlan& p,
+                                          const float2* tw, float s, int tid, int nthr) {
+  if constexpr (NSTAT > 0) static_fft<NSTAT, NL, LF>(lds, L.nl, L.es, L.ls, tw, s, tid, nthr);
+  else lds_fft(lds, L, p, tw, s, tid, nthr);
+}
+
+}  // namespace wo
+
+// Transform lengths with compiled FFT stages (lateral sizes and axial sizes).
+#define WO_LATERAL_SIZES(X) X(64) X(128) X(160) X(192) X(240) X(256) X(320) X(384) X(480) X(512) X(1024)
+#define WO_AXIAL_SIZES(X) X(16) X(24) X(32) X(48) X(64) X(96)
+#define WO_ALL_SIZES(X) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(160) X(192) X(240) X(256) X(320) X(384) X(480) X(512) X(1024)

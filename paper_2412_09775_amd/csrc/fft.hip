@@ -17,6 +17,7 @@ __device__ __forceinline__ long group_row(long r, long rpg, long stride) {
   return g * stride + (r - g * rpg);
 }
 
+template <int NS>
 __global__ __launch_bounds__(1024) void k_rows_r2c(const float* __restrict__ in,
                                                    float2* __restrict__ out, int X, RowGroups g,
                                                    FftPlan plan, int lines_per_wg, long nlines) {
@@ -25,7 +26,6 @@ __global__ __launch_bounds__(1024) void k_rows_r2c(const float* __restrict__ in,
   float2* buf = smem + X;
   __shared__ long rin[2 * 64], rout[2 * 64];
   const int tid = threadIdx.x, nthr = blockDim.x;
-  fill_twiddles(tw, X, tid, nthr);
   const long nrows = g.rows_per_group * g.ngroups;
   const long line0 = (long)blockIdx.x * lines_per_wg;
   const int nl = (int)min((long)lines_per_wg, nlines - line0);
@@ -40,9 +40,9 @@ __global__ __launch_bounds__(1024) void k_rows_r2c(const float* __restrict__ in,
     const float a = in[rin[2 * l] * X + i];
     const float b = rin[2 * l + 1] >= 0 ? in[rin[2 * l + 1] * X + i] : 0.f;
     return make_float2(a, b);
-  });
+  }, [&] { fill_twiddles(tw, X, tid, nthr); });
   __syncthreads();
-  lds_fft(buf, LdsLines{nl, 1, X, false}, plan, tw, -1.f, tid, nthr);
+  fft_lines<NS, 0, false>(buf, LdsLines{nl, 1, X, false}, plan, tw, -1.f, tid, nthr);
   const int Xh = X / 2 + 1;
 #pragma unroll
   for (int i = 0; i < kEmax; ++i) {
@@ -59,6 +59,7 @@ __global__ __launch_bounds__(1024) void k_rows_r2c(const float* __restrict__ in,
   }
 }
 
+template <int NS>
 __global__ __launch_bounds__(1024) void k_rows_c2r(const float2* __restrict__ in,
                                                    float* __restrict__ out, int X, RowGroups g,
                                                    FftPlan plan, int lines_per_wg, long nlines,
@@ -68,7 +69,6 @@ __global__ __launch_bounds__(1024) void k_rows_c2r(const float2* __restrict__ in
   float2* buf = smem + X;
   __shared__ long rin[2 * 64], rout[2 * 64];
   const int tid = threadIdx.x, nthr = blockDim.x;
-  fill_twiddles(tw, X, tid, nthr);
   const long nrows = g.rows_per_group * g.ngroups;
   const long line0 = (long)blockIdx.x * lines_per_wg;
   const int nl = (int)min((long)lines_per_wg, nlines - line0);
@@ -88,9 +88,9 @@ __global__ __launch_bounds__(1024) void k_rows_c2r(const float2* __restrict__ in
     if (kk == 0 || 2 * kk == X) { A.y = 0.f; B.y = 0.f; }   // Re of the inverse ignores them
     if (mirror) { A.y = -A.y; B.y = -B.y; }
     return make_float2(A.x - B.y, A.y + B.x);
-  });
+  }, [&] { fill_twiddles(tw, X, tid, nthr); });
   __syncthreads();
-  lds_fft(buf, LdsLines{nl, 1, X, false}, plan, tw, 1.f, tid, nthr);
+  fft_lines<NS, 0, false>(buf, LdsLines{nl, 1, X, false}, plan, tw, 1.f, tid, nthr);
   scatter_from_lds(buf, nl * X, tid, nthr, [&](int e, float2 v) {
     const int l = e / X, i = e - l * X;
     out[rout[2 * l] * X + i] = v.x * scale;
@@ -106,6 +106,11 @@ static int lines_per_wg_for(int X) {
   return L;
 }
 
+#define WO_CASE_ROWS(K, NN)                                                                      \
+  case NN:                                                                                       \
+    hipLaunchKernelGGL((K<NN>), dim3((unsigned)nwg), dim3(thr), lds, s, WO_ROWS_ARGS);          \
+    break;
+
 hipError_t launch_rows_r2c(const float* in, float2* out, int X, const RowGroups& g, hipStream_t s) {
   FftPlan plan;
   if (!make_plan(X, &plan)) return hipErrorInvalidValue;
@@ -115,9 +120,16 @@ hipError_t launch_rows_r2c(const float* in, float2* out, int X, const RowGroups&
   const long nwg = (nlines + L - 1) / L;
   const int thr = threads_for((long)L * X);
   const size_t lds = (size_t)(X + L * X) * sizeof(float2);
-  { ScopedTiming _t("k_rows_r2c", s);
-  hipLaunchKernelGGL(k_rows_r2c, dim3((unsigned)nwg), dim3(thr), lds, s, in, out, X, g, plan, L,
-                     nlines); }
+  ScopedTiming _t("k_rows_r2c", s);
+#define WO_ROWS_ARGS in, out, X, g, plan, L, nlines
+#define X_(NN) WO_CASE_ROWS(k_rows_r2c, NN)
+  switch (X) {
+    WO_LATERAL_SIZES(X_)
+    default:
+      hipLaunchKernelGGL((k_rows_r2c<0>), dim3((unsigned)nwg), dim3(thr), lds, s, WO_ROWS_ARGS);
+  }
+#undef X_
+#undef WO_ROWS_ARGS
   return hipGetLastError();
 }
 
@@ -131,22 +143,30 @@ hipError_t launch_rows_c2r(const float2* in, float* out, int X, const RowGroups&
   const long nwg = (nlines + L - 1) / L;
   const int thr = threads_for((long)L * X);
   const size_t lds = (size_t)(X + L * X) * sizeof(float2);
-  { ScopedTiming _t("k_rows_c2r", s);
-  hipLaunchKernelGGL(k_rows_c2r, dim3((unsigned)nwg), dim3(thr), lds, s, in, out, X, g, plan, L,
-                     nlines, scale); }
+  ScopedTiming _t("k_rows_c2r", s);
+#define WO_ROWS_ARGS in, out, X, g, plan, L, nlines, scale
+#define X_(NN) WO_CASE_ROWS(k_rows_c2r, NN)
+  switch (X) {
+    WO_LATERAL_SIZES(X_)
+    default:
+      hipLaunchKernelGGL((k_rows_c2r<0>), dim3((unsigned)nwg), dim3(thr), lds, s, WO_ROWS_ARGS);
+  }
+#undef X_
+#undef WO_ROWS_ARGS
   return hipGetLastError();
 }
 
 // ------------------------------------------------------------------ columns
 
-__global__ __launch_bounds__(1024) void k_cols(float2* __restrict__ data, int N, long M, int W,
+template <int NS, int WS>
+__global__ __launch_bounds__(1024) void k_cols(float2* __restrict__ data, int N, long M, int Wrt,
                                                long tiles_m, long planes_per_group,
                                                long group_stride, FftPlan plan, float sign) {
+  const int W = WS > 0 ? WS : Wrt;
   extern __shared__ float2 smem[];
   float2* tw = smem;
   float2* buf = smem + N;
   const int tid = threadIdx.x, nthr = blockDim.x;
-  fill_twiddles(tw, N, tid, nthr);
   const long bid = blockIdx.x;
   const long tile = bid % tiles_m;
   const long plane = bid / tiles_m;
@@ -157,9 +177,9 @@ __global__ __launch_bounds__(1024) void k_cols(float2* __restrict__ data, int N,
   gather_to_lds(buf, N * W, tid, nthr, [&](int e) {
     const int n = e / W, w = e - n * W;
     return w < weff ? base[(long)n * M + m0 + w] : make_float2(0.f, 0.f);
-  });
+  }, [&] { fill_twiddles(tw, N, tid, nthr); });
   __syncthreads();
-  lds_fft(buf, LdsLines{W, W, 1, true}, plan, tw, sign, tid, nthr);
+  fft_lines<NS, WS, true>(buf, LdsLines{W, W, 1, true}, plan, tw, sign, tid, nthr);
   scatter_from_lds(buf, N * W, tid, nthr, [&](int e, float2 v) {
     const int n = e / W, w = e - n * W;
     if (w < weff) base[(long)n * M + m0 + w] = v;
@@ -176,18 +196,43 @@ static int tile_width(int n, int ch) {
   return W;
 }
 
+// Static tile width for a compiled length: 16 columns when the tile fits the
+// per-workgroup element budget, else the largest power of two that does.
+constexpr int static_tile_width(int n) {
+  int W = 16;
+  while (W > 1 && W * n > kMaxElems) W /= 2;
+  return W;
+}
+
 hipError_t launch_cols(float2* data, int N, long M, long planes_per_group, long group_stride,
                        long ngroups, float sign, hipStream_t s, const char* tag) {
   FftPlan plan;
   if (!make_plan(N, &plan)) return hipErrorInvalidValue;
-  const int W = tile_width(N, 1);
+  int W = tile_width(N, 1);
+  ScopedTiming _t(tag, s);
+#define X_(NN)                                                                                  \
+  case NN:                                                                                      \
+    if ((long)(NN + static_tile_width(NN) * NN) * (long)sizeof(float2) <= lds_limit_bytes()) {   \
+      constexpr int WS = static_tile_width(NN);                                                 \
+      const long tiles = (M + WS - 1) / WS;                                                     \
+      hipLaunchKernelGGL((k_cols<NN, WS>), dim3((unsigned)(tiles * planes_per_group * ngroups)), \
+                         dim3(threads_for((long)NN * WS)), (size_t)(NN + NN * WS) * sizeof(float2), s, \
+                         data, N, M, WS, tiles, planes_per_group, group_stride, plan, sign);     \
+      return hipGetLastError();                                                                 \
+    }                                                                                           \
+    break;
+  switch (N) {
+    WO_ALL_SIZES(X_)
+    default:
+      break;
+  }
+#undef X_
   const long tiles = (M + W - 1) / W;
   const long nwg = tiles * planes_per_group * ngroups;
   const int thr = threads_for((long)N * W);
   const size_t lds = (size_t)(N + N * W) * sizeof(float2);
-  { ScopedTiming _t(tag, s);
-  hipLaunchKernelGGL(k_cols, dim3((unsigned)nwg), dim3(thr), lds, s, data, N, M, W, tiles,
-                     planes_per_group, group_stride, plan, sign); }
+  hipLaunchKernelGGL((k_cols<0, 0>), dim3((unsigned)nwg), dim3(thr), lds, s, data, N, M, W, tiles,
+                     planes_per_group, group_stride, plan, sign);
   return hipGetLastError();
 }
 
@@ -301,7 +346,7 @@ __device__ __forceinline__ void freq_op(float2* cell, long cs, HF H, int Crt, in
 
 constexpr int kTfPrefetch = 8;   // transfer-function values a thread may hold in registers
 
-template <int P, int CT>
+template <int P, int CT, int NS>
 __global__ __launch_bounds__(1024) void k_zop(float2* __restrict__ spec,
                                               const float2* __restrict__ tf, int C, int Z, long M,
                                               int slots, int W, long tiles_m, FftPlan plan,
@@ -340,7 +385,6 @@ __global__ __launch_bounds__(1024) void k_zop(float2* __restrict__ spec,
       }
     }
   }
-  fill_twiddles(tw, Z, tid, nthr);
   {
     // element e = (ch, z, w) of the global tile goes to LDS [z][ch][w]
     float2 t[kEmax];
@@ -353,6 +397,7 @@ __global__ __launch_bounds__(1024) void k_zop(float2* __restrict__ spec,
         t[i] = w < weff ? sp[((long)ch * Z + z) * M + m0 + w] : make_float2(0.f, 0.f);
       }
     }
+    fill_twiddles(tw, Z, tid, nthr);
 #pragma unroll
     for (int i = 0; i < kEmax; ++i) {
       const int e = tid + i * nthr;
@@ -364,7 +409,7 @@ __global__ __launch_bounds__(1024) void k_zop(float2* __restrict__ spec,
     }
   }
   __syncthreads();
-  lds_fft(buf, LdsLines{cin * W, CH * W, 1, true}, plan, tw, -1.f, tid, nthr);
+  fft_lines<NS, 0, true>(buf, LdsLines{cin * W, CH * W, 1, true}, plan, tw, -1.f, tid, nthr);
   if (prefetch) {
 #pragma unroll
     for (int i = 0; i < kTfPrefetch; ++i) {
@@ -391,7 +436,7 @@ __global__ __launch_bounds__(1024) void k_zop(float2* __restrict__ spec,
     }
   }
   __syncthreads();
-  lds_fft(buf, LdsLines{cout * W, CH * W, 1, true}, plan, tw, 1.f, tid, nthr);
+  fft_lines<NS, 0, true>(buf, LdsLines{cout * W, CH * W, 1, true}, plan, tw, 1.f, tid, nthr);
   {
     float2 t[kEmax];
 #pragma unroll
@@ -419,8 +464,19 @@ template <int P, int CT>
 static void zop_launch(long nwg, int thr, size_t lds, hipStream_t s, float2* spec, const float2* tf,
                        int C, int Z, long M, int slots, int W, long tiles, FftPlan plan, int mode,
                        float eta, const float* bg, float inv_n, float nf) {
-  hipLaunchKernelGGL((k_zop<P, CT>), dim3((unsigned)nwg), dim3(thr), lds, s, spec, tf, C, Z, M, slots,
-                     W, tiles, plan, mode, eta, bg, inv_n, nf);
+#define X_(NN)                                                                                   \
+  case NN:                                                                                       \
+    hipLaunchKernelGGL((k_zop<P, CT, NN>), dim3((unsigned)nwg), dim3(thr), lds, s, spec, tf, C, Z, M, \
+                       slots, W, tiles, plan, mode, eta, bg, inv_n, nf);                         \
+    return;
+  switch (Z) {
+    WO_AXIAL_SIZES(X_)
+    default:
+      break;
+  }
+#undef X_
+  hipLaunchKernelGGL((k_zop<P, CT, 0>), dim3((unsigned)nwg), dim3(thr), lds, s, spec, tf, C, Z, M,
+                     slots, W, tiles, plan, mode, eta, bg, inv_n, nf);
 }
 
 hipError_t launch_zop(float2* spec, const float2* tf, int C, int P, int Z, long M, int slots,

@@ -83,6 +83,7 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
 // field, field 1 = B).  Workgroups of plane 0 also write the tile's share of
 // the pupil sum (sum S P^2 for label-free, sum P^2 for fluorescence) to
 // partials[patch * tiles_x + tile].
+template <int NS>
 __global__ __launch_bounds__(1024) void k_tf_fields_y(const DevOptics* __restrict__ opt,
                                                       Sampling sm, float2* __restrict__ ab,
                                                       double* __restrict__ partials, int W,
@@ -148,7 +149,7 @@ __global__ __launch_bounds__(1024) void k_tf_fields_y(const DevOptics* __restric
     if (tid == 0) partials[patch * tiles_x + tile] = tot;
   }
   __syncthreads();
-  lds_fft(buf, LdsLines{nf * W, nf * W, 1, true}, plan, tw, 1.f, tid, nthr);
+  fft_lines<NS, 0, true>(buf, LdsLines{nf * W, nf * W, 1, true}, plan, tw, 1.f, tid, nthr);
   scatter_from_lds(buf, Y * nf * W, tid, nthr, [&](int e, float2 v) {
     const int ky = e / (nf * W);
     const int r = e - ky * nf * W;
@@ -176,9 +177,20 @@ hipError_t launch_tf_fields_y(const DevOptics* opt, const Sampling& sm, int npat
   const long nwg = tiles * sm.nz * (long)npatch;
   const int thr = threads_for((long)sm.ny * nf * W);
   const size_t lds = (size_t)(sm.ny + sm.ny * nf * W) * sizeof(float2);
-  { ScopedTiming _t("k_tf_fields_y", s);
-  hipLaunchKernelGGL(k_tf_fields_y, dim3((unsigned)nwg), dim3(thr), lds, s, opt, sm, ab, partials, W,
-                     tiles, plan); }
+  ScopedTiming _t("k_tf_fields_y", s);
+#define X_(NN)                                                                                   \
+  case NN:                                                                                       \
+    hipLaunchKernelGGL((k_tf_fields_y<NN>), dim3((unsigned)nwg), dim3(thr), lds, s, opt, sm, ab,  \
+                       partials, W, tiles, plan);                                                \
+    return hipGetLastError();
+  switch (sm.ny) {
+    WO_LATERAL_SIZES(X_)
+    default:
+      break;
+  }
+#undef X_
+  hipLaunchKernelGGL((k_tf_fields_y<0>), dim3((unsigned)nwg), dim3(thr), lds, s, opt, sm, ab, partials,
+                     W, tiles, plan);
   return hipGetLastError();
 }
 
@@ -191,6 +203,7 @@ __device__ __forceinline__ double pupil_total(const double* partials, long tiles
   return t;
 }
 
+template <int NS>
 __global__ __launch_bounds__(1024) void k_tf_rows_lf(const double* __restrict__ partials,
                                                      long tiles_x, Sampling sm,
                                                      const float2* __restrict__ ab,
@@ -219,7 +232,7 @@ __global__ __launch_bounds__(1024) void k_tf_rows_lf(const double* __restrict__ 
     return src[(row0 + r) * X + i];
   });
   __syncthreads();
-  lds_fft(buf, LdsLines{2 * nr, 1, X, false}, plan, tw, 1.f, tid, nthr);
+  fft_lines<NS, 0, false>(buf, LdsLines{2 * nr, 1, X, false}, plan, tw, 1.f, tid, nthr);
   const float cs = (float)(1.0 / ((double)X * (double)Y * ibg_s));
   for (int e = tid; e < nr * X; e += nthr) {
     const int r = e / X, i = e - r * X;
@@ -227,7 +240,7 @@ __global__ __launch_bounds__(1024) void k_tf_rows_lf(const double* __restrict__ 
     buf[2 * r * X + i] = cscale(cmulconj(b, a), cs);
   }
   __syncthreads();
-  lds_fft(buf, LdsLines{nr, 1, 2 * X, false}, plan, tw, -1.f, tid, nthr);
+  fft_lines<NS, 0, false>(buf, LdsLines{nr, 1, 2 * X, false}, plan, tw, -1.f, tid, nthr);
   float2* op = out + patch * patch_stride;
   for (int e = tid; e < nr * Xh; e += nthr) {
     const int r = e / Xh, k = e - r * Xh;
@@ -256,15 +269,27 @@ hipError_t launch_tf_rows_labelfree(const double* partials, const Sampling& sm, 
   const long nwg = wpp * npatch;
   const int thr = threads_for(2L * R * sm.nx);
   const size_t lds = (size_t)(sm.nx + 2 * R * sm.nx) * sizeof(float2);
-  { ScopedTiming _t("k_tf_rows_lf", s);
-  hipLaunchKernelGGL(k_tf_rows_lf, dim3((unsigned)nwg), dim3(thr), lds, s, partials, tiles_x, sm, ab,
-                     out, patch_stride, pstride, zstride, R, wpp, plan); }
+  ScopedTiming _t("k_tf_rows_lf", s);
+#define X_(NN)                                                                                   \
+  case NN:                                                                                       \
+    hipLaunchKernelGGL((k_tf_rows_lf<NN>), dim3((unsigned)nwg), dim3(thr), lds, s, partials, tiles_x, \
+                       sm, ab, out, patch_stride, pstride, zstride, R, wpp, plan);               \
+    return hipGetLastError();
+  switch (sm.nx) {
+    WO_LATERAL_SIZES(X_)
+    default:
+      break;
+  }
+#undef X_
+  hipLaunchKernelGGL((k_tf_rows_lf<0>), dim3((unsigned)nwg), dim3(thr), lds, s, partials, tiles_x, sm,
+                     ab, out, patch_stride, pstride, zstride, R, wpp, plan);
   return hipGetLastError();
 }
 
 // ------------------------------------------------------------------ rows: fluorescence
 
 // h: [patch][z][y][x] complex (after the inverse Y pass); out: [patch][z][y][Xh]
+template <int NS>
 __global__ __launch_bounds__(1024) void k_tf_rows_fl(const double* __restrict__ partials,
                                                      long tiles_x, Sampling sm,
                                                      const float2* __restrict__ h,
@@ -289,7 +314,7 @@ __global__ __launch_bounds__(1024) void k_tf_rows_fl(const double* __restrict__ 
     return l < nrows ? src[(row0 + l) * X + i] : make_float2(0.f, 0.f);
   });
   __syncthreads();
-  lds_fft(buf, LdsLines{2 * np, 1, X, false}, plan, tw, 1.f, tid, nthr);
+  fft_lines<NS, 0, false>(buf, LdsLines{2 * np, 1, X, false}, plan, tw, 1.f, tid, nthr);
   const double norm = 1.0 / ((double)Z * (double)X * (double)Y * ibg_s);
   const float nm = (float)norm;
   for (int e = tid; e < np * X; e += nthr) {
@@ -298,7 +323,7 @@ __global__ __launch_bounds__(1024) void k_tf_rows_fl(const double* __restrict__ 
     buf[2 * q * X + i] = make_float2((u.x * u.x + u.y * u.y) * nm, (v.x * v.x + v.y * v.y) * nm);
   }
   __syncthreads();
-  lds_fft(buf, LdsLines{np, 1, 2 * X, false}, plan, tw, -1.f, tid, nthr);
+  fft_lines<NS, 0, false>(buf, LdsLines{np, 1, 2 * X, false}, plan, tw, -1.f, tid, nthr);
   float2* op = out + patch * rpp * Xh;
   for (int e = tid; e < np * Xh; e += nthr) {
     const int q = e / Xh, k = e - q * Xh;
@@ -324,9 +349,20 @@ hipError_t launch_tf_rows_fluor(const double* partials, const Sampling& sm, int 
   const long nwg = wpp * npatch;
   const int thr = threads_for(2L * Q * sm.nx);
   const size_t lds = (size_t)(sm.nx + 2 * Q * sm.nx) * sizeof(float2);
-  { ScopedTiming _t("k_tf_rows_fl", s);
-  hipLaunchKernelGGL(k_tf_rows_fl, dim3((unsigned)nwg), dim3(thr), lds, s, partials, tiles_x, sm, h,
-                     out, Q, wpp, plan); }
+  ScopedTiming _t("k_tf_rows_fl", s);
+#define X_(NN)                                                                                   \
+  case NN:                                                                                       \
+    hipLaunchKernelGGL((k_tf_rows_fl<NN>), dim3((unsigned)nwg), dim3(thr), lds, s, partials, tiles_x, \
+                       sm, h, out, Q, wpp, plan);                                                \
+    return hipGetLastError();
+  switch (sm.nx) {
+    WO_LATERAL_SIZES(X_)
+    default:
+      break;
+  }
+#undef X_
+  hipLaunchKernelGGL((k_tf_rows_fl<0>), dim3((unsigned)nwg), dim3(thr), lds, s, partials, tiles_x, sm, h,
+                     out, Q, wpp, plan);
   return hipGetLastError();
 }
 
@@ -334,6 +370,7 @@ hipError_t launch_tf_rows_fluor(const double* partials, const Sampling& sm, int 
 
 // uw: [patch][2][Z][M] (phase, absorption half spectra after the Y pass);
 // tf: [patch][5][4][Z][M], H_cp = Re(kappa_cp) U + Im(kappa_cp) V after the Z transform.
+template <int NS>
 __global__ __launch_bounds__(1024) void k_tf_pol5_z(const DevOptics* __restrict__ opt, int Z,
                                                     long M, const float2* __restrict__ uw,
                                                     float2* __restrict__ tf, int W, long tiles_m,
@@ -370,7 +407,7 @@ __global__ __launch_bounds__(1024) void k_tf_pol5_z(const DevOptics* __restrict_
     }
   }
   __syncthreads();
-  lds_fft(buf, LdsLines{2 * W, 2 * W, 1, true}, plan, tw, -1.f, tid, nthr);
+  fft_lines<NS, 0, true>(buf, LdsLines{2 * W, 2 * W, 1, true}, plan, tw, -1.f, tid, nthr);
   float kr[20], ki[20];
   const DevOptics& o = opt[patch];
 #pragma unroll
@@ -402,9 +439,20 @@ hipError_t launch_tf_pol5_z(const DevOptics* opt, const Sampling& sm, int npatch
   const long nwg = tiles * npatch;
   const int thr = threads_for(2L * sm.nz * W);
   const size_t lds = (size_t)(sm.nz + 2 * sm.nz * W) * sizeof(float2);
-  { ScopedTiming _t("k_tf_pol5_z", s);
-  hipLaunchKernelGGL(k_tf_pol5_z, dim3((unsigned)nwg), dim3(thr), lds, s, opt, sm.nz, M, uw, tf, W,
-                     tiles, plan); }
+  ScopedTiming _t("k_tf_pol5_z", s);
+#define X_(NN)                                                                                   \
+  case NN:                                                                                       \
+    hipLaunchKernelGGL((k_tf_pol5_z<NN>), dim3((unsigned)nwg), dim3(thr), lds, s, opt, sm.nz, M, uw, \
+                       tf, W, tiles, plan);                                                      \
+    return hipGetLastError();
+  switch (sm.nz) {
+    WO_AXIAL_SIZES(X_)
+    default:
+      break;
+  }
+#undef X_
+  hipLaunchKernelGGL((k_tf_pol5_z<0>), dim3((unsigned)nwg), dim3(thr), lds, s, opt, sm.nz, M, uw, tf, W,
+                     tiles, plan);
   return hipGetLastError();
 }
 

@@ -192,7 +192,10 @@ def test_gradients_at_tile_shape_match_finite_differences(gpu_lib):
     print("[case] tile-shape FD gradients, 8 patches", flush=True)
     _, grad = gpu_lib.midband_loss_grad(starts, torch.from_numpy(stacks).cuda(), np.full(8, eta), nu_c)
     for i, o in enumerate(starts):
-        fd = at.fd_gradient(o, stacks[i].astype(np.float64), eta, nu_c, steps=[1e-3, 1e-4, 1e-3, 1e-3],
+        # small steps: the C1 smoothstep pupil edge has a discontinuous second
+        # derivative, so Richardson-extrapolated differences need h well below
+        # the edge width (a 1e-3 rad tilt step leaves ~1e-3 truncation error here)
+        fd = at.fd_gradient(o, stacks[i].astype(np.float64), eta, nu_c, steps=[1e-4, 1e-5, 1e-5, 1e-5],
                             which=(0, 1, 2))
         err = np.max(np.abs(grad[i][:3] - fd[:3])) / np.max(np.abs(fd[:3]))
         print(f"  patch {i}: gpu {grad[i][:3]} fd {fd[:3]} rel {err:.2e}", flush=True)
