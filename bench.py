@@ -102,6 +102,8 @@ def main():
     ap.add_argument("--cnn-train-patches", type=int, default=16384)
     ap.add_argument("--cnn-epochs", type=int, default=8)
     ap.add_argument("--cnn-tune-iters", type=int, default=20)
+    ap.add_argument("--restore-tiles", type=int, default=64)
+    ap.add_argument("--restore-graph", type=int, default=1, choices=(0, 1, 2))
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for HBM counters)")
     args = ap.parse_args()
@@ -218,8 +220,16 @@ def main():
     }
 
     if not args.no_autotune:
-        out["autotune"] = autotune_section(api, torch, dev, args.tune_patches, args.tune_iters,
-                                           args.cnn_train_patches, args.cnn_epochs, args.cnn_tune_iters)
+        net, train = None, None
+        if args.cnn_train_patches > 0:
+            net, train = train_cnn(api, torch, dev, args.cnn_train_patches, args.cnn_epochs)
+        out["autotune"] = autotune_section(api, torch, dev, args.tune_patches, args.tune_iters, net,
+                                           args.cnn_tune_iters)
+        if train:
+            out["autotune"]["cnn_training"] = train
+        if args.restore_tiles > 0:
+            out["restore"] = restore_section(api, torch, dev, net, args.restore_tiles, args.cnn_tune_iters,
+                                             args.tune_iters, args.restore_graph)
     if args.calibrate_copy:
         src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
@@ -247,13 +257,44 @@ TUNE_HI = (2.5, 1.3, math.radians(32.0), 1.0)
 TUNE_MASK = 0b0101
 
 
-def autotune_section(api, torch, dev, n, iters, cnn_patches, cnn_epochs, cnn_iters):
+def thin_sigma_max_sq(tf):
+    """max over 2D frequencies of the largest eigenvalue of H^H H for a thin bank
+    (n, Z, 2, Y, Xh): the 2x2 Gram matrix of the two property columns."""
+    h0, h1 = tf[:, :, 0], tf[:, :, 1]
+    a = (h0.abs() ** 2).sum(dim=1)
+    b = (h1.abs() ** 2).sum(dim=1)
+    m = (h0.conj() * h1).sum(dim=1).abs()
+    return float(((a + b) / 2 + (((a - b) / 2) ** 2 + m ** 2).sqrt()).max())
+
+
+def norm_err(th, truth):
+    """Median over patches of max_j |theta_j - truth_j| / range_j, and per component."""
+    e = np.abs(np.asarray(th)[:, :3] - truth) / TUNE_RANGE
+    return float(np.median(e.max(axis=1))), [round(float(x), 4) for x in np.median(e, axis=0)]
+
+
+def prior_draws(rng, n):
+    return np.stack([rng.uniform(-2, 2, n), rng.uniform(1.0, 1.3, n),
+                     rng.uniform(0.0, math.radians(30.0), n)], 1)
+
+
+def grid_starts(n, na):
+    """8 starts per patch: defocus {-1.5, -0.5, 0.5, 1.5} um x tilt {7.5, 22.5} deg."""
+    grid = np.stack(np.meshgrid([-1.5, -0.5, 0.5, 1.5], [math.radians(7.5), math.radians(22.5)],
+                                indexing="ij"), -1).reshape(-1, 2)
+    theta0 = np.zeros((n, 8, 4))
+    theta0[:, :, 0] = grid[None, :, 0]
+    theta0[:, :, 1] = na
+    theta0[:, :, 2] = grid[None, :, 1]
+    return theta0
+
+
+def autotune_section(api, torch, dev, n, iters, net, cnn_iters):
     """Patches/s of the batched GPU auto-tune (single start, 8-start multistart and
     CNN-initialised) and the median normalised parameter error |theta - truth| / range."""
     import synth
     rng = np.random.default_rng(4001)
-    truth = np.stack([rng.uniform(-2, 2, n), rng.uniform(1.0, 1.3, n),
-                      rng.uniform(0.0, math.radians(30.0), n)], 1)
+    truth = prior_draws(rng, n)
     opts_true = [api.Optics(**dict(TUNE, defocus=t[0], na_det=t[1], tilt_zenith=t[2])) for t in truth]
     objs = np.stack([synth.thin_cells((TUNE["ny"], TUNE["nx"]), TUNE["dx"], 20, seed=5000 + i)
                      for i in range(n)])
@@ -262,26 +303,14 @@ def autotune_section(api, torch, dev, n, iters, cnn_patches, cnn_epochs, cnn_ite
     d = torch.from_numpy(synth.poisson_gaussian(clean.cpu().numpy(), seed=4002)).to(dev)
     del tf_true, clean
     nominal = api.Optics(**TUNE)
-    tf_nom = api.transfer_function([nominal], device=dev)
-    eta = 1e-2 * float((tf_nom.abs() ** 2).sum(dim=2).max())
+    eta = 1e-2 * thin_sigma_max_sq(api.transfer_function([nominal], device=dev))
     nu_c = (TUNE["na_det"] + TUNE["na_ill"]) / TUNE["wavelength"]
     starts = [api.Optics(**dict(TUNE, tilt_zenith=math.radians(15.0))) for _ in range(n)]
-
-    def err(th):
-        e = np.abs(th[:, :3] - truth) / TUNE_RANGE
-        return float(np.median(e.max(axis=1))), [float(x) for x in np.median(e, axis=0)]
 
     res = {"workload": f"{n} patches 32x128x128, {iters} Adam iterations, hipGraph replay, "
                        "tuning defocus and zenith tilt"}
     for label, M in (("single_start", 1), ("multistart_8", 8)):
-        theta0 = None
-        if M > 1:
-            grid = np.stack(np.meshgrid([-1.5, -0.5, 0.5, 1.5], [math.radians(7.5), math.radians(22.5)],
-                                        indexing="ij"), -1).reshape(-1, 2)
-            theta0 = np.zeros((n, M, 4))
-            theta0[:, :, 0] = grid[None, :, 0]
-            theta0[:, :, 1] = TUNE["na_det"]
-            theta0[:, :, 2] = grid[None, :, 1]
+        theta0 = grid_starts(n, TUNE["na_det"]) if M > 1 else None
         ws = torch.empty(api.tune_workspace_size(starts, M), dtype=torch.uint8, device=dev)
         api.autotune(starts[:1], d[:1], eta, iters=2, lr=TUNE_LR, lo=TUNE_LO, hi=TUNE_HI, multistart=M,
                      theta0=None if theta0 is None else theta0[:1], nu_c=nu_c, use_graph=True, ws=ws,
@@ -294,31 +323,14 @@ def autotune_section(api, torch, dev, n, iters, cnn_patches, cnn_epochs, cnn_ite
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         th = np.array([[o.defocus, o.na_det, o.tilt_zenith, o.tilt_azimuth] for o in out])
-        med, per = err(th)
+        med, per = norm_err(th, truth)
         res[label] = {"patches_per_s": n / dt, "seconds": round(dt, 3), "starts": M,
-                      "median_norm_param_err": round(med, 4),
-                      "median_norm_err_defocus_na_tilt": [round(x, 4) for x in per]}
+                      "median_norm_param_err": round(med, 4), "median_norm_err_defocus_na_tilt": per}
         del ws
         print(f"[bench] autotune {label}: {n / dt:.1f} patches/s, median err {med:.3f}",
               file=sys.stderr, flush=True)
 
-    # learned initialiser: train on simulated 32x64x64 patches (not timed in patches/s),
-    # then CNN prediction + a short single-start auto-tune on the same tiles
-    if cnn_patches > 0:
-        from paper_2412_09775_amd import learned_init
-        tmpl64 = api.Optics(**dict(TUNE, ny=64, nx=64, edge_width=0.25))
-        t0 = time.perf_counter()
-        stacks, theta = learned_init.simulate(tmpl64, cnn_patches, seed=6001, device=dev)
-        torch.cuda.synchronize()
-        t_sim = time.perf_counter() - t0
-        net = learned_init.LearnedInit(dev, seed=0)
-        t0 = time.perf_counter()
-        hist = net.train(stacks, theta, epochs=cnn_epochs, batch=64, lr=1e-3)
-        torch.cuda.synchronize()
-        t_train = time.perf_counter() - t0
-        del stacks
-        print(f"[bench] cnn trained: {cnn_patches} patches x {cnn_epochs} epochs in {t_train:.1f}s, "
-              f"loss {hist[0]:.3f} -> {hist[-1]:.3f}", file=sys.stderr, flush=True)
+    if net is not None:
         ws = torch.empty(api.tune_workspace_size(starts, 1), dtype=torch.uint8, device=dev)
         net.predict(d[:8])
         api.autotune(starts[:1], d[:1], eta, iters=2, lr=TUNE_LR, lo=TUNE_LO, hi=TUNE_HI, nu_c=nu_c,
@@ -333,19 +345,114 @@ def autotune_section(api, torch, dev, n, iters, cnn_patches, cnn_epochs, cnn_ite
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         th = np.array([[o.defocus, o.na_det, o.tilt_zenith, o.tilt_azimuth] for o in out])
-        med, per = err(th)
-        med0, per0 = err(np.concatenate([pred, np.zeros((n, 1))], 1))
-        res["cnn_init"] = {"patches_per_s": n / dt, "seconds": round(dt, 3), "tune_iters": cnn_iters,
-                           "median_norm_param_err": round(med, 4),
-                           "median_norm_err_defocus_na_tilt": [round(x, 4) for x in per],
-                           "cnn_only_median_norm_err_defocus_na_tilt": [round(x, 4) for x in per0],
-                           "train": {"patches": cnn_patches, "epochs": cnn_epochs, "batch": 64,
-                                     "simulate_s": round(t_sim, 2), "train_s": round(t_train, 2),
-                                     "loss_first_last": [round(hist[0], 4), round(hist[-1], 4)]}}
+        med, per = norm_err(th, truth)
+        med0, per0 = norm_err(pred, truth)
         ms = res["multistart_8"]["patches_per_s"]
-        res["cnn_init"]["speedup_vs_multistart_8"] = round(n / dt / ms, 2)
+        res["cnn_init"] = {"patches_per_s": n / dt, "seconds": round(dt, 3), "tune_iters": cnn_iters,
+                           "median_norm_param_err": round(med, 4), "median_norm_err_defocus_na_tilt": per,
+                           "cnn_only_median_norm_err_defocus_na_tilt": per0,
+                           "speedup_vs_multistart_8": round(n / dt / ms, 2)}
         print(f"[bench] cnn init: {n / dt:.1f} patches/s, median err {med:.3f} (cnn only {med0:.3f})",
               file=sys.stderr, flush=True)
+    return res
+
+
+def train_cnn(api, torch, dev, patches, epochs):
+    """The learned initialiser trained on forward-model patches 32x64x64 (not part of
+    any patches/s figure); a quarter of the patches keep only their central 16 planes
+    and a quarter 24, as tiles with fewer planes present them."""
+    from paper_2412_09775_amd import learned_init
+    tmpl64 = api.Optics(**dict(TUNE, ny=64, nx=64, edge_width=0.25))
+    t0 = time.perf_counter()
+    stacks, theta = learned_init.simulate(tmpl64, patches, seed=6001, device=dev)
+    learned_init.clear_outer_planes(stacks, seed=6002, keeps=(16, 24, 32, 32))
+    torch.cuda.synchronize()
+    t_sim = time.perf_counter() - t0
+    net = learned_init.LearnedInit(dev, seed=0)
+    t0 = time.perf_counter()
+    hist = net.train(stacks, theta, epochs=epochs, batch=64, lr=1e-3)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    del stacks
+    print(f"[bench] cnn trained: {patches} patches x {epochs} epochs in {t_train:.1f}s, "
+          f"loss {hist[0]:.3f} -> {hist[-1]:.3f}", file=sys.stderr, flush=True)
+    return net, {"patches": patches, "epochs": epochs, "batch": 64, "simulate_s": round(t_sim, 2),
+                 "train_s": round(t_train, 2), "loss_first_last": [round(hist[0], 4), round(hist[-1], 4)]}
+
+
+RESTORE_Z = (16, 24, 32, 48, 64)
+RESTORE_YX = (128, 160, 192, 240, 256, 320, 384, 480, 512)
+
+
+def restore_section(api, torch, dev, net, ntiles, cnn_iters, ms_iters, graph_mode):
+    """Shift-variant restoration of uneven tiles (Z in 16..64, Y, X in 128..512, each
+    tile its own true optics): CNN initialisation + a short auto-tune, against plain
+    8-start multistart; each arm ends with the thin reconstruction of every tile, all
+    inside one wo_restore_tiles call."""
+    from paper_2412_09775_amd import learned_init
+    rng = np.random.default_rng(5001)
+    shapes = [(int(rng.choice(RESTORE_Z)), int(rng.choice(RESTORE_YX)), int(rng.choice(RESTORE_YX)))
+              for _ in range(ntiles)]
+    truth = prior_draws(rng, ntiles)
+
+    def tile_optics(shape, **kw):
+        z, y, x = shape
+        # soft pupil edge of the same absolute width as 0.5 px on a 128 x 128 tile
+        return api.Optics(**dict(TUNE, nz=z, ny=y, nx=x, edge_width=0.5 * max(y, x) / 128.0, **kw))
+
+    tiles, etas, nucs, nominal = [], [], [], []
+    for i, (shape, t) in enumerate(zip(shapes, truth)):
+        ot = tile_optics(shape, defocus=t[0], na_det=t[1], tilt_zenith=t[2])
+        cells = api.synth_thin_cells(1, shape[1], shape[2], TUNE["dx"],
+                                     max(1, round(20 * shape[1] * shape[2] / 128 ** 2)), 7000 + i, dev)
+        d = api.forward([ot], api.transfer_function([ot], device=dev), cells)[0]
+        api.add_gaussian_noise(d, 0.0317, 8000 + i)   # Poisson-Gaussian at I_bg 1000, read 2 e-
+        tiles.append(d)
+        on = tile_optics(shape)
+        nominal.append(on)
+        etas.append(1e-2 * thin_sigma_max_sq(api.transfer_function([on], device=dev)))
+        nucs.append((on.na_det + on.na_ill) / on.wavelength)
+    torch.cuda.synchronize()
+    vox = sum(z * y * x for z, y, x in shapes)
+    res = {"workload": f"{ntiles} tiles, Z in {list(RESTORE_Z)}, Y and X in {list(RESTORE_YX)} "
+                       f"({vox / 1e6:.1f} M voxels, {len(set(shapes))} distinct shapes), thin model, "
+                       f"tuning defocus and zenith tilt, thin reconstruction of every tile; "
+                       f"use_graph={graph_mode}"}
+
+    def run(label, M, iters, theta0, predict):
+        ws = torch.empty(api.tune_workspace_size(nominal, M), dtype=torch.uint8, device=dev)
+        fo = torch.empty(sum(2 * y * x for _, y, x in shapes), dtype=torch.float32, device=dev)
+        small = [tile_optics((16, 128, 128))]
+        api.restore_tiles(small, [tiles[0].new_zeros((16, 128, 128))], etas[:1], iters=1, lr=TUNE_LR,
+                          lo=TUNE_LO, hi=TUNE_HI, multistart=M, mask=TUNE_MASK, use_graph=graph_mode)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        if predict:
+            pred = net.predict(learned_init.network_input(tiles))
+            theta0 = np.zeros((ntiles, 1, 4))
+            theta0[:, 0, :3] = np.clip(pred, np.array(TUNE_LO[:3]), np.array(TUNE_HI[:3]))
+        out, loss, _, _, f = api.restore_tiles(nominal, tiles, etas, iters=iters, lr=TUNE_LR, lo=TUNE_LO,
+                                               hi=TUNE_HI, multistart=M, theta0=theta0, nu_c=nucs,
+                                               mask=TUNE_MASK, use_graph=graph_mode, ws=ws, f_out=fo)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        th = np.array([[o.defocus, o.na_det, o.tilt_zenith, o.tilt_azimuth] for o in out])
+        med, per = norm_err(th, truth)
+        r = {"tiles_per_s": ntiles / dt, "voxels_per_s": vox / dt, "seconds": round(dt, 3), "starts": M,
+             "tune_iters": iters, "median_norm_param_err": round(med, 4),
+             "median_norm_err_defocus_na_tilt": per}
+        if predict:
+            r["cnn_only_median_norm_err_defocus_na_tilt"] = norm_err(pred, truth)[1]
+        print(f"[bench] restore {label}: {ntiles / dt:.1f} tiles/s, median err {med:.3f}",
+              file=sys.stderr, flush=True)
+        del ws, fo
+        return r
+
+    res["multistart_8"] = run("multistart_8", 8, ms_iters, grid_starts(ntiles, TUNE["na_det"]), False)
+    if net is not None:
+        res["cnn_init"] = run("cnn_init", 1, cnn_iters, None, True)
+        res["cnn_init"]["speedup_vs_multistart_8"] = round(
+            res["cnn_init"]["tiles_per_s"] / res["multistart_8"]["tiles_per_s"], 2)
     return res
 
 

@@ -151,11 +151,19 @@ int wo_adjoint(const wo_optics* o, int32_t n, const void* tf, const float* r, fl
  * function is recomputed every iteration.  Soft pupil edges (edge_width > 0)
  * are needed for non-zero NA and tilt gradients. */
 
-/* Workspace bytes for wo_midband_loss_grad (starts = 1) or wo_autotune. */
+/* Unlike the calls above, the calls of this section accept patches of uneven
+ * shapes (each o[i] its own nz >= 2, ny, nx, dz, dy, dx): the stacks are
+ * packed, patch i's [nz_i][ny_i][nx_i] floats following patch i-1's, and the
+ * patches that share a sampling are processed by the same launches
+ * (shift-variant processing of overlapping tiles, Methods "Cell-scale optical
+ * pooled screen data" and "Organelle-scale optical pooled screen data").  */
+
+/* Workspace bytes for wo_midband_loss_grad (starts = 1), wo_autotune or
+ * wo_restore_tiles (0 if any patch is not WO_MODEL_LABELFREE_THIN). */
 size_t wo_tune_workspace_size(const wo_optics* o, int32_t n, int32_t starts);
 
-/* Loss and dL/dtheta at each patch's optics.  d: device [n][nz][ny][nx]
- * stacks; eta, nu_c: host [n] (nu_c may be NULL or <= 0 for the default);
+/* Loss and dL/dtheta at each patch's optics.  d: device, packed stacks;
+ * eta, nu_c: host [n] (nu_c may be NULL or <= 0 for the default);
  * loss_out: host [n]; grad_out: host [n][4] or NULL.  Synchronises `stream`
  * before returning. */
 int wo_midband_loss_grad(const wo_optics* o, int32_t n, const float* d, const double* eta,
@@ -165,7 +173,11 @@ int wo_midband_loss_grad(const wo_optics* o, int32_t n, const float* d, const do
 typedef struct wo_autotune_opts {
   int32_t iters;           /* Adam iterations (the paper uses 100) */
   int32_t multistart;      /* starts per patch, M >= 1; the lowest final loss wins */
-  int32_t use_graph;       /* capture one iteration in a HIP graph and replay it */
+  int32_t use_graph;       /* 0: plain launches; 1: one iteration of every patch
+                              captured in a HIP graph and replayed `iters` times;
+                              2: the whole call (iterations, final loss and, for
+                              wo_restore_tiles, the reconstruction) captured in
+                              one HIP graph and launched once */
   int32_t tune_mask;       /* bit j set: theta_j is tuned */
   double lr[4];            /* Adam learning rates per parameter */
   double lo[4], hi[4];     /* box for theta (NA is further capped inside the shell) */
@@ -173,16 +185,31 @@ typedef struct wo_autotune_opts {
   const double* nu_c;      /* host [n] band cutoffs, or NULL for the default */
   double* all_theta_out;   /* host [n][M][4] final theta of every start, or NULL */
   double* all_loss_out;    /* host [n][M] final loss of every start, or NULL */
+  int32_t branches;        /* graph modes: concurrent branches the shape groups
+                              are spread over (0: 4; at most 8), balanced by
+                              voxels x starts */
 } wo_autotune_opts;
 
 /* Adam (beta 0.9, 0.999, eps 1e-8) on theta for opts->iters iterations, every
  * patch and start in one batched launch sequence; theta is clipped to the box
  * after each step.  On return o[i] holds the best start's theta and
- * loss_out[i] (host, may be NULL) its loss at that theta.  d: device
- * [n][nz][ny][nx]; eta: host [n].  Synchronises `stream` before returning. */
+ * loss_out[i] (host, may be NULL) its loss at that theta.  d: device, packed
+ * stacks; eta: host [n].  Not reentrant across host threads (calls
+ * serialise on a library lock).  Synchronises `stream` before returning. */
 int wo_autotune(wo_optics* o, int32_t n, const float* d, const double* eta,
                 const wo_autotune_opts* opts, double* loss_out, void* ws, size_t ws_bytes,
                 void* stream);
+
+/* Shift-variant restoration of uneven tiles: wo_autotune, then the thin-model
+ * Tikhonov reconstruction (Eq. tls_solution, one Z x 2 system per lateral
+ * frequency, eta[i]) of every tile at its best start's final theta, written
+ * to f_out (device, packed [2][ny_i][nx_i] per tile: phase, absorption; the
+ * same values as wo_transfer_function + wo_reconstruct at that theta).  With
+ * opts->use_graph = 2 the whole call is one graph launch.  The workspace size
+ * is wo_tune_workspace_size(o, n, multistart).  f_out NULL: WO_EINVAL. */
+int wo_restore_tiles(wo_optics* o, int32_t n, const float* d, const double* eta,
+                     const wo_autotune_opts* opts, double* loss_out, float* f_out, void* ws,
+                     size_t ws_bytes, void* stream);
 
 /* ---------------------------------------------------------------- learned initialiser
  * Not in the paper: a small 3D CNN that regresses normalised (defocus, NA_det,
@@ -231,6 +258,19 @@ int wo_conv3d_weight_grad(const uint16_t* x, const uint16_t* gz, int32_t N, int3
 int wo_synth_thin_cells(float* out, int32_t n, int32_t ny, int32_t nx, double pixel, int32_t ncells,
                         uint64_t seed, void* stream);
 int wo_add_gaussian_noise(float* x, int64_t n, double sigma, uint64_t seed, void* stream);
+
+/* Fixed-size network input from a stack of any size: out[i][z][y][x] =
+ * in[i][z + z0][y + y0][x + x0] where that voxel exists and, if keep_z (device
+ * [n]) is not NULL, |2 z - (oz - 1)| < keep_z[i] (only the central keep_z[i]
+ * planes); 0 elsewhere.  Offsets may be negative (zero padding).  A thin stack
+ * with fewer planes than the network input is, zero-padded symmetrically,
+ * the same as a full stack with its outer planes cleared (the planes share
+ * z_k = dz (k - (nz-1)/2)); keep_z produces that case for training.  in: device
+ * [n][nz][ny][nx]; out: device [n][oz][oy][ox]; in == out only with equal
+ * shapes and zero offsets (else WO_EALIAS). */
+int wo_crop_stacks(const float* in, int32_t n, int32_t nz, int32_t ny, int32_t nx, float* out,
+                   int32_t oz, int32_t oy, int32_t ox, int32_t z0, int32_t y0, int32_t x0,
+                   const int32_t* keep_z, void* stream);
 
 /* Instrumentation (not part of the method): while enabled, every kernel the
  * library launches is bracketed by HIP events on the stream it runs on.

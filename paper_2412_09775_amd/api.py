@@ -32,9 +32,10 @@ OP_ADJOINT = 3
 SYMBOLS = ("wo_bank_shape", "wo_workspace_size", "wo_transfer_function", "wo_forward",
            "wo_reconstruct", "wo_adjoint", "wo_strerror", "wo_version", "wo_timing_enable",
            "wo_timing_report", "wo_tune_workspace_size", "wo_midband_loss_grad", "wo_autotune",
+           "wo_restore_tiles",
            "wo_cnn_param_count", "wo_cnn_workspace_size", "wo_cnn_forward", "wo_cnn_gradient",
            "wo_cnn_train_step", "wo_conv3d_forward", "wo_conv3d_input_grad", "wo_conv3d_weight_grad",
-           "wo_synth_thin_cells", "wo_add_gaussian_noise")
+           "wo_synth_thin_cells", "wo_add_gaussian_noise", "wo_crop_stacks")
 
 _FIELDS = ("model", "nz", "ny", "nx", "dz", "dy", "dx", "wavelength", "na_ill", "na_det",
            "n_medium", "defocus", "tilt_zenith", "tilt_azimuth", "edge_width", "swing")
@@ -73,7 +74,7 @@ class WoAutotuneOpts(ctypes.Structure):
                 ("lr", ctypes.c_double * 4), ("lo", ctypes.c_double * 4), ("hi", ctypes.c_double * 4),
                 ("theta0", ctypes.POINTER(ctypes.c_double)), ("nu_c", ctypes.POINTER(ctypes.c_double)),
                 ("all_theta_out", ctypes.POINTER(ctypes.c_double)),
-                ("all_loss_out", ctypes.POINTER(ctypes.c_double))]
+                ("all_loss_out", ctypes.POINTER(ctypes.c_double)), ("branches", ctypes.c_int32)]
 
 
 class WoError(RuntimeError):
@@ -112,6 +113,8 @@ def load(path: str = LIB_PATH):
     lib.wo_tune_workspace_size.restype = sz
     lib.wo_midband_loss_grad.argtypes = [op, i32, vp, dp, dp, dp, dp, vp, sz, vp]
     lib.wo_autotune.argtypes = [op, i32, vp, dp, ctypes.POINTER(WoAutotuneOpts), dp, vp, sz, vp]
+    lib.wo_restore_tiles.argtypes = [op, i32, vp, dp, ctypes.POINTER(WoAutotuneOpts), dp, vp, vp, sz,
+                                     vp]
     i64, u64, f64 = ctypes.c_int64, ctypes.c_uint64, ctypes.c_double
     lib.wo_cnn_param_count.restype = i64
     lib.wo_cnn_workspace_size.argtypes = [i32, i32, i32, i32]
@@ -126,6 +129,7 @@ def load(path: str = LIB_PATH):
     lib.wo_conv3d_weight_grad.argtypes = conv + [vp, sz, vp]
     lib.wo_synth_thin_cells.argtypes = [vp, i32, i32, i32, f64, i32, u64, vp]
     lib.wo_add_gaussian_noise.argtypes = [vp, i64, f64, u64, vp]
+    lib.wo_crop_stacks.argtypes = [vp, i32, i32, i32, i32, vp, i32, i32, i32, i32, i32, i32, vp, vp]
     lib.wo_timing_enable.argtypes = [ctypes.c_int]
     lib.wo_timing_report.argtypes = [ctypes.c_char_p, ctypes.c_size_t]
     for name in SYMBOLS:
@@ -293,14 +297,24 @@ def tune_workspace_size(optics, starts: int = 1) -> int:
     return int(load().wo_tune_workspace_size(arr, len(arr), starts))
 
 
+def pack_stacks(stacks):
+    """One contiguous float32 device tensor from a [n, Z, Y, X] tensor or a list of
+    [Z_i, Y_i, X_i] tensors (uneven tiles), patch after patch."""
+    import torch
+    if isinstance(stacks, (list, tuple)):
+        return torch.cat([s.contiguous().reshape(-1) for s in stacks])
+    return stacks.contiguous()
+
+
 def midband_loss_grad(optics, d, eta, nu_c=None, ws=None, stream=None):
-    """Mid-band loss and dL/dtheta per patch (numpy arrays (n,), (n, 4))."""
+    """Mid-band loss and dL/dtheta per patch (numpy arrays (n,), (n, 4)); `d` as in
+    pack_stacks (patches may differ in shape)."""
     import numpy as np
     import torch
     lib = load()
     arr = optics_array(optics)
     n = len(arr)
-    d = d.contiguous()
+    d = pack_stacks(d)
     need = tune_workspace_size(optics, 1)
     if ws is None or ws.numel() < need:
         ws = torch.empty(need, dtype=torch.uint8, device=d.device)
@@ -315,24 +329,22 @@ def midband_loss_grad(optics, d, eta, nu_c=None, ws=None, stream=None):
     return loss, grad
 
 
-def autotune(optics, d, eta, iters=100, lr=PAPER_LR, lo=(-1e300,) * 4, hi=(1e300,) * 4,
-             mask=0b0111, multistart=1, theta0=None, nu_c=None, use_graph=False, ws=None,
-             stream=None):
-    """Adam auto-tune of theta for every patch; returns (optics list, loss, all_theta, all_loss)."""
+def _tune_call(fn, name, optics, d, eta, iters, lr, lo, hi, mask, multistart, theta0, nu_c, use_graph,
+               branches, ws, stream, extra):
     import copy
     import numpy as np
     import torch
-    lib = load()
     optics = list(optics) if isinstance(optics, (list, tuple)) else [optics]
     arr = optics_array(optics)
     n = len(arr)
     M = int(multistart)
-    d = d.contiguous()
+    d = pack_stacks(d)
     need = tune_workspace_size(optics, M)
     if ws is None or ws.numel() < need:
         ws = torch.empty(need, dtype=torch.uint8, device=d.device)
     opts = WoAutotuneOpts()
-    opts.iters, opts.multistart, opts.use_graph, opts.tune_mask = int(iters), M, int(bool(use_graph)), int(mask)
+    opts.iters, opts.multistart, opts.use_graph, opts.tune_mask = int(iters), M, int(use_graph), int(mask)
+    opts.branches = int(branches)
     for j in range(4):
         opts.lr[j], opts.lo[j], opts.hi[j] = float(lr[j]), float(lo[j]), float(hi[j])
     keep = []
@@ -350,9 +362,9 @@ def autotune(optics, d, eta, iters=100, lr=PAPER_LR, lo=(-1e300,) * 4, hi=(1e300
     opts.all_loss_out = all_loss.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
     eta_a, eta_p = _dbl(np.broadcast_to(eta, (n,)))
     loss = np.zeros(n)
-    _check(lib.wo_autotune(arr, n, _ptr(d), eta_p, ctypes.byref(opts),
-                           loss.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), _ptr(ws), ws.numel(),
-                           _stream(stream)), "wo_autotune")
+    _check(fn(arr, n, _ptr(d), eta_p, ctypes.byref(opts),
+              loss.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), *extra, _ptr(ws), ws.numel(),
+              _stream(stream)), name)
     out = []
     for i, o in enumerate(optics):
         oo = copy.copy(o)
@@ -363,6 +375,36 @@ def autotune(optics, d, eta, iters=100, lr=PAPER_LR, lo=(-1e300,) * 4, hi=(1e300
                 setattr(oo, f, getattr(arr[i], f))
         out.append(oo)
     return out, loss, all_theta, all_loss
+
+
+def autotune(optics, d, eta, iters=100, lr=PAPER_LR, lo=(-1e300,) * 4, hi=(1e300,) * 4,
+             mask=0b0111, multistart=1, theta0=None, nu_c=None, use_graph=False, branches=0, ws=None,
+             stream=None):
+    """Adam auto-tune of theta for every patch; returns (optics list, loss, all_theta, all_loss).
+    `d` as in pack_stacks; use_graph 0/False, 1/True (one iteration replayed) or 2 (one launch)."""
+    return _tune_call(load().wo_autotune, "wo_autotune", optics, d, eta, iters, lr, lo, hi, mask,
+                      multistart, theta0, nu_c, use_graph, branches, ws, stream, ())
+
+
+def restore_tiles(optics, d, eta, iters=20, lr=PAPER_LR, lo=(-1e300,) * 4, hi=(1e300,) * 4,
+                  mask=0b0111, multistart=1, theta0=None, nu_c=None, use_graph=2, branches=0,
+                  f_out=None, ws=None, stream=None):
+    """Auto-tune then thin reconstruction of uneven tiles.  Returns (optics list, loss,
+    all_theta, all_loss, f) with f a list of [2, Y_i, X_i] views into one packed buffer."""
+    import torch
+    optics = list(optics) if isinstance(optics, (list, tuple)) else [optics]
+    sizes = [2 * int(_get(o, "ny")) * int(_get(o, "nx")) for o in optics]
+    d = pack_stacks(d)
+    if f_out is None:
+        f_out = torch.empty(sum(sizes), dtype=torch.float32, device=d.device)
+    lib = load()
+    res = _tune_call(lib.wo_restore_tiles, "wo_restore_tiles", optics, d, eta, iters, lr, lo, hi, mask,
+                     multistart, theta0, nu_c, use_graph, branches, ws, stream, (_ptr(f_out),))
+    views, off = [], 0
+    for o, sz in zip(optics, sizes):
+        views.append(f_out[off:off + sz].view(2, int(_get(o, "ny")), int(_get(o, "nx"))))
+        off += sz
+    return (*res, views)
 
 
 # ---------------------------------------------------------------- autograd wrappers
@@ -508,3 +550,19 @@ def add_gaussian_noise(x, sigma, seed, stream=None):
     _check(load().wo_add_gaussian_noise(_ptr(x), x.numel(), float(sigma), int(seed), _stream(stream)),
            "wo_add_gaussian_noise")
     return x
+
+
+def crop_stacks(x, out_shape, offsets=(0, 0, 0), keep_z=None, out=None, stream=None):
+    """Windows (n, oz, oy, ox) of stacks x (n, Z, Y, X) at `offsets`, zero outside the
+    input and outside the central keep_z[i] planes (see ``wo_crop_stacks``)."""
+    import torch
+    n, Z, Y, X = x.shape
+    oz, oy, ox = out_shape
+    if out is None:
+        out = torch.empty((n, oz, oy, ox), dtype=torch.float32, device=x.device)
+    keep = None
+    if keep_z is not None:
+        keep = torch.as_tensor(keep_z, dtype=torch.int32).to(x.device)
+    _check(load().wo_crop_stacks(_ptr(x), n, Z, Y, X, _ptr(out), oz, oy, ox, *[int(v) for v in offsets],
+                                 _ptr(keep), _stream(stream)), "wo_crop_stacks")
+    return out

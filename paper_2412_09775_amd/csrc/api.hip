@@ -2,6 +2,7 @@
 #include <math.h>
 #include <string.h>
 
+#include <algorithm>
 #include <complex>
 #include <map>
 #include <mutex>
@@ -279,17 +280,20 @@ int run_linear(const wo_optics* o, int32_t n, const Shape& s, const float2* tf, 
 
 // ---------------------------------------------------------------- auto-tune
 
+// Workspace of one group of equally sampled patches, np patches x starts
+// virtual patches (byte offsets from the group's base).
 struct TuneLayout {
-  int nv;
+  int np, nv;
   long tiles, lbpp, dwpp;
   size_t off_opt, off_st, off_D, off_bank, off_ab, off_gam, off_pp, off_lp, off_dp, off_gp, off_ip,
-      total;
+      off_ropt, off_reta, total;
 };
 
 TuneLayout tune_layout(const wo_optics* o, int32_t n, int32_t starts) {
   TuneLayout L;
   const Sampling sm = sampling_of(o);
   const long Z = o->nz, Y = o->ny, X = o->nx, Xh = X / 2 + 1;
+  L.np = n;
   L.nv = n * starts;
   const int W = tf_tile_width(sm);
   L.tiles = (X + W - 1) / W;
@@ -308,19 +312,78 @@ TuneLayout tune_layout(const wo_optics* o, int32_t n, int32_t starts) {
   L.off_dp = take((size_t)L.nv * L.dwpp * sizeof(double));
   L.off_gp = take((size_t)L.nv * Z * L.tiles * 4 * sizeof(double));
   L.off_ip = take((size_t)L.nv * L.tiles * 4 * sizeof(double));
+  L.off_ropt = take((size_t)n * sizeof(DevOptics));
+  L.off_reta = take((size_t)n * sizeof(float));
   L.total = b;
   return L;
 }
 
-// Number of lateral frequencies (full spectrum) with nu_c/8 <= |nu| <= nu_c/4.
+// Patches that share a sampling are tuned by the same launches; a batch of
+// uneven tiles forms one group per distinct shape, each with its own
+// workspace slice.  `work` (voxels x starts) balances the graph branches.
+struct TuneGroup {
+  const wo_optics* rep;
+  std::vector<int> idx;  // patch indices in the call, ascending
+  TuneLayout L;
+  size_t base;
+  double work;
+};
+
+std::vector<TuneGroup> tune_groups(const wo_optics* o, int32_t n, int32_t starts, size_t* total) {
+  std::vector<TuneGroup> g;
+  for (int i = 0; i < n; ++i) {
+    size_t k = 0;
+    while (k < g.size() && !same_sampling(g[k].rep, &o[i])) ++k;
+    if (k == g.size()) g.push_back(TuneGroup{&o[i], {}, TuneLayout{}, 0, 0.0});
+    g[k].idx.push_back(i);
+  }
+  size_t b = 0;
+  for (auto& t : g) {
+    t.L = tune_layout(t.rep, (int)t.idx.size(), starts);
+    t.base = b;
+    b += t.L.total;
+    t.work = (double)t.idx.size() * starts * t.rep->nz * t.rep->ny * t.rep->nx;
+  }
+  if (total) *total = b;
+  return g;
+}
+
+// Runs of consecutive patch indices inside a group: (first local index, length).
+std::vector<std::pair<int, int>> index_runs(const std::vector<int>& idx) {
+  std::vector<std::pair<int, int>> r;
+  for (int j = 0; j < (int)idx.size();) {
+    int k = j + 1;
+    while (k < (int)idx.size() && idx[k] == idx[k - 1] + 1) ++k;
+    r.push_back({j, k - j});
+    j = k;
+  }
+  return r;
+}
+
+// Element offsets of packed per-patch arrays: stacks (nz ny nx) or thin
+// reconstructions (2 ny nx).
+std::vector<size_t> packed_offsets(const wo_optics* o, int32_t n, bool stacks) {
+  std::vector<size_t> off(n + 1, 0);
+  for (int i = 0; i < n; ++i)
+    off[i + 1] = off[i] + (size_t)(stacks ? o[i].nz : 2) * o[i].ny * o[i].nx;
+  return off;
+}
+
+// Number of lateral frequencies (full spectrum) with nu_c/8 <= |nu| <= nu_c/4,
+// evaluated with the same expression as the loss kernel; rows and columns
+// beyond nu_c/4 (plus one sample of margin) cannot be in the band.
 double band_count(const wo_optics* o, double nu_c) {
   long cnt = 0;
   const double vy = 1.0 / ((double)o->ny * o->dy), vx = 1.0 / ((double)o->nx * o->dx);
+  const double rmax = nu_c / 4.0;
+  const long my = (long)(rmax / vy) + 1, mx = (long)(rmax / vx) + 1;
   for (int ky = 0; ky < o->ny; ++ky) {
     const int sy = ky < (o->ny + 1) / 2 ? ky : ky - o->ny;
+    if (labs((long)sy) > my) continue;
     const double fy = sy * vy;
     for (int kx = 0; kx < o->nx; ++kx) {
       const int sx = kx < (o->nx + 1) / 2 ? kx : kx - o->nx;
+      if (labs((long)sx) > mx) continue;
       const double fx = sx * vx;
       const double r = sqrt(fy * fy + fx * fx);
       if (r >= nu_c / 8.0 && r <= nu_c / 4.0) ++cnt;
@@ -343,12 +406,13 @@ DevOptics dev_optics(const wo_optics& o) {
   return d;
 }
 
-// One auto-tune iteration for all virtual patches (update = 0: loss and
-// gradient only).
-int tune_iteration(const wo_optics* o, const TuneLayout& L, char* w, int starts, int update,
-                   hipStream_t hs) {
-  const Sampling sm = sampling_of(o);
-  const long Z = o->nz, Y = o->ny, Xh = o->nx / 2 + 1;
+// One auto-tune iteration of every virtual patch of a group (update = 0: loss
+// and gradient only).
+int tune_iteration(const TuneGroup& g, char* ws, int starts, int update, hipStream_t hs) {
+  const TuneLayout& L = g.L;
+  char* w = ws + g.base;
+  const Sampling sm = sampling_of(g.rep);
+  const long Z = sm.nz, Y = sm.ny, Xh = sm.nx / 2 + 1;
   const long plane = Y * Xh;
   DevOptics* dopt = (DevOptics*)(w + L.off_opt);
   TuneState* st = (TuneState*)(w + L.off_st);
@@ -367,73 +431,63 @@ int tune_iteration(const wo_optics* o, const TuneLayout& L, char* w, int starts,
   WO_TRY(launch_cols(bank, (int)Y, Xh, 2 * Z, 2 * Z, nv, -1.f, hs, "k_cols_y_tf"));
   WO_TRY(launch_loss_grad(dopt, st, sm, nv, D, bank, lp, starts, hs));
   WO_TRY(launch_cols(bank, (int)Y, Xh, 2 * Z, 2 * Z, nv, 1.f, hs, "k_cols_y_grad"));
-  RowGroups g{2 * Z * Y, 2 * Z * Y, 2 * Z * Y, nv};
-  WO_TRY(launch_rows_c2r(bank, gam, o->nx, g, 1.f, hs));
+  RowGroups rg{2 * Z * Y, 2 * Z * Y, 2 * Z * Y, nv};
+  WO_TRY(launch_rows_c2r(bank, gam, sm.nx, rg, 1.f, hs));
   WO_TRY(launch_tf_rows_bwd(pp, sm, nv, ab, gam, dp, hs));
   WO_TRY(launch_tf_grad_y(dopt, sm, nv, ab, gp, ip, hs));
   WO_TRY(launch_adam(dopt, st, sm, nv, pp, lp, dp, gp, ip, update, hs));
   return WO_OK;
 }
 
-int validate_thin(const wo_optics* o, int32_t n) {
-  int st = validate(o, n);
-  if (st) return st;
-  if (o->model != WO_MODEL_LABELFREE_THIN) return WO_EUNSUPPORTED;
-  return WO_OK;
-}
-
-// Set-up shared by the loss/gradient call and the auto-tune: per-virtual-patch
-// optics and tune state, and the 2D spectra of the data stacks.
-int tune_setup(const wo_optics* o, int32_t n, int starts, const double* theta0, const float* d,
-               const double* eta, const double* nu_c, const double* lr, const double* lo,
-               const double* hi, int mask, const TuneLayout& L, char* w, hipStream_t hs) {
-  const int nv = L.nv;
-  std::vector<DevOptics> hopt(nv);
-  std::vector<TuneState> hst(nv);
-  for (int v = 0; v < nv; ++v) {
-    const int i = v / starts;
-    hopt[v] = dev_optics(o[i]);
-    if (theta0) {
-      hopt[v].defocus = theta0[4 * v + 0];
-      hopt[v].na_det = theta0[4 * v + 1];
-      hopt[v].tilt_zenith = theta0[4 * v + 2];
-      hopt[v].tilt_azimuth = theta0[4 * v + 3];
-    }
-    TuneState& t = hst[v];
-    memset(&t, 0, sizeof(t));
-    for (int j = 0; j < 4; ++j) {
-      t.lr[j] = lr ? lr[j] : 0.0;
-      t.lo[j] = lo ? lo[j] : -1e300;
-      t.hi[j] = hi ? hi[j] : 1e300;
-    }
-    t.eta = eta[i];
-    t.nu_c = (nu_c && nu_c[i] > 0) ? nu_c[i] : (o[i].na_det + o[i].na_ill) / o[i].wavelength;
-    t.band_count = band_count(&o[i], t.nu_c);
-    if (t.band_count < 1) return WO_EINVAL;
-    t.mask = mask;
-  }
-  // every virtual patch must describe valid optics at its start
-  for (int v = 0; v < nv; ++v) {
-    wo_optics ov = o[v / starts];
-    ov.defocus = hopt[v].defocus;
-    ov.na_det = hopt[v].na_det;
-    ov.tilt_zenith = hopt[v].tilt_zenith;
-    ov.tilt_azimuth = hopt[v].tilt_azimuth;
-    int stt = check_optics(&ov);
-    if (stt) return stt;
-  }
-  WO_TRY(launch_set_params((DevOptics*)(w + L.off_opt), hopt.data(), nv, hs));
-  WO_TRY(launch_set_tune((TuneState*)(w + L.off_st), hst.data(), nv, hs));
-  const long Z = o->nz, Y = o->ny;
+// Thin-model reconstruction of every patch of a group at its best start's
+// final theta: transfer function at that theta, per-frequency Tikhonov solve
+// of the Z x 2 system with the patch's eta, inverse 2D transform into the
+// packed output [2][ny][nx] of each patch.  Consumes the data spectra.
+int tune_restore(const TuneGroup& g, char* ws, int starts, float* f_out, const size_t* foff,
+                 hipStream_t hs) {
+  const TuneLayout& L = g.L;
+  char* w = ws + g.base;
+  const Sampling sm = sampling_of(g.rep);
+  const long Z = sm.nz, Y = sm.ny, X = sm.nx, Xh = X / 2 + 1;
+  const long plane = Y * Xh;
+  const int np = L.np;
+  DevOptics* ropt = (DevOptics*)(w + L.off_ropt);
+  float* reta = (float*)(w + L.off_reta);
   float2* D = (float2*)(w + L.off_D);
-  RowGroups g{Z * Y, Z * Y, Z * Y, n};
-  WO_TRY(launch_rows_r2c(d, D, o->nx, g, hs));
-  WO_TRY(launch_cols(D, (int)Y, o->nx / 2 + 1, Z, Z, n, -1.f, hs, "k_cols_y_data"));
+  float2* bank = (float2*)(w + L.off_bank);
+  float2* ab = (float2*)(w + L.off_ab);
+  double* pp = (double*)(w + L.off_pp);
+  WO_TRY(launch_pick_best((const DevOptics*)(w + L.off_opt), (const TuneState*)(w + L.off_st), starts,
+                          np, ropt, reta, hs));
+  WO_TRY(launch_tf_fields_y(ropt, sm, np, ab, pp, hs));
+  WO_TRY(launch_tf_rows_labelfree(pp, sm, np, ab, bank, 2 * Z * plane, plane, 2 * plane, hs));
+  WO_TRY(launch_cols(bank, (int)Y, Xh, 2 * Z, 2 * Z, np, -1.f, hs, "k_cols_y_tf"));
+  const double nfull = (double)Y * X;
+  WO_TRY(launch_op2d(D, bank, (int)Z, 2, plane, (int)Z, np, kModeSolve, 0.f, nullptr,
+                     (float)(1.0 / nfull), nfull, hs, reta));
+  WO_TRY(launch_cols(D, (int)Y, Xh, 2, Z, np, 1.f, hs, "k_cols_y_inv"));
+  for (auto r : index_runs(g.idx)) {
+    RowGroups rg{2 * Y, Z * Y, 2 * Y, r.second};
+    WO_TRY(launch_rows_c2r(D + (size_t)r.first * Z * plane, f_out + foff[g.idx[r.first]], (int)X, rg,
+                           1.f, hs));
+  }
   return WO_OK;
 }
 
-// Largest theta box that keeps every pupil strictly inside the shell and the
-// support inside the lateral band, intersected with the caller's box.
+int validate_thin(const wo_optics* o, int32_t n) {
+  if (!o || n < 1) return WO_EINVAL;
+  for (int i = 0; i < n; ++i) {
+    int st = check_sampling(&o[i]);
+    if (st) return st;
+    if (o[i].model != WO_MODEL_LABELFREE_THIN || o[i].nz < 2) return WO_EUNSUPPORTED;
+    st = check_optics(&o[i]);
+    if (st) return st;
+  }
+  return WO_OK;
+}
+
+// Largest theta box that keeps the detection pupil strictly inside the shell,
+// intersected with the caller's box.
 void clamp_box(const wo_optics* o, double lo[4], double hi[4]) {
   const double km = o->n_medium / o->wavelength;
   const double dnu = fmin(1.0 / (o->nx * o->dx), 1.0 / (o->ny * o->dy));
@@ -441,6 +495,266 @@ void clamp_box(const wo_optics* o, double lo[4], double hi[4]) {
   const double na_max = (km - hw) * o->wavelength * (1.0 - 1e-9);
   if (hi[1] > na_max) hi[1] = na_max;
   if (lo[1] < 0.0) lo[1] = 0.0;
+}
+
+// Set-up of one group: per-virtual-patch optics and tune state, and the 2D
+// spectra of the group's data stacks (read from the packed input `d`).
+int tune_setup(const wo_optics* o, const TuneGroup& g, int starts, const double* theta0,
+               const float* d, const size_t* doff, const double* eta, const double* nu_c,
+               const double* lr, const double* lo, const double* hi, int mask, char* ws,
+               hipStream_t hs) {
+  const TuneLayout& L = g.L;
+  char* w = ws + g.base;
+  const int np = L.np, nv = L.nv;
+  std::vector<DevOptics> hopt(nv);
+  std::vector<TuneState> hst(nv);
+  for (int j = 0; j < np; ++j) {
+    const int i = g.idx[j];
+    double blo[4], bhi[4];
+    for (int k = 0; k < 4; ++k) {
+      blo[k] = lo ? lo[k] : -1e300;
+      bhi[k] = hi ? hi[k] : 1e300;
+    }
+    if (lo && hi) clamp_box(&o[i], blo, bhi);
+    const double nuc = (nu_c && nu_c[i] > 0) ? nu_c[i] : (o[i].na_det + o[i].na_ill) / o[i].wavelength;
+    const double bc = band_count(&o[i], nuc);
+    if (bc < 1) return WO_EINVAL;
+    for (int s = 0; s < starts; ++s) {
+      const int v = j * starts + s;
+      const long gv = (long)i * starts + s;
+      hopt[v] = dev_optics(o[i]);
+      if (theta0) {
+        hopt[v].defocus = theta0[4 * gv + 0];
+        hopt[v].na_det = theta0[4 * gv + 1];
+        hopt[v].tilt_zenith = theta0[4 * gv + 2];
+        hopt[v].tilt_azimuth = theta0[4 * gv + 3];
+      }
+      TuneState& t = hst[v];
+      memset(&t, 0, sizeof(t));
+      for (int k = 0; k < 4; ++k) {
+        t.lr[k] = lr ? lr[k] : 0.0;
+        t.lo[k] = blo[k];
+        t.hi[k] = bhi[k];
+      }
+      t.eta = eta[i];
+      t.nu_c = nuc;
+      t.band_count = bc;
+      t.mask = mask;
+      // every virtual patch must describe valid optics at its start
+      wo_optics ov = o[i];
+      ov.defocus = hopt[v].defocus;
+      ov.na_det = hopt[v].na_det;
+      ov.tilt_zenith = hopt[v].tilt_zenith;
+      ov.tilt_azimuth = hopt[v].tilt_azimuth;
+      const int stt = check_optics(&ov);
+      if (stt) return stt;
+    }
+  }
+  WO_TRY(launch_set_params((DevOptics*)(w + L.off_opt), hopt.data(), nv, hs));
+  WO_TRY(launch_set_tune((TuneState*)(w + L.off_st), hst.data(), nv, hs));
+  const long Z = g.rep->nz, Y = g.rep->ny, Xh = g.rep->nx / 2 + 1;
+  float2* D = (float2*)(w + L.off_D);
+  for (auto r : index_runs(g.idx)) {
+    RowGroups rg{Z * Y, Z * Y, Z * Y, r.second};
+    WO_TRY(launch_rows_r2c(d + doff[g.idx[r.first]], D + (size_t)r.first * Z * Y * Xh, g.rep->nx, rg,
+                           hs));
+  }
+  WO_TRY(launch_cols(D, (int)Y, Xh, Z, Z, np, -1.f, hs, "k_cols_y_data"));
+  return WO_OK;
+}
+
+// Library streams for graph capture: one origin stream and up to kMaxBranches
+// branch streams, default priority, created on first use and kept.
+constexpr int kMaxBranches = 8;
+struct CaptureStreams {
+  hipStream_t cap = nullptr;
+  hipStream_t br[kMaxBranches] = {};
+  hipEvent_t fork = nullptr, join[kMaxBranches] = {}, ready = nullptr, done = nullptr;
+};
+std::mutex g_tune_mu;
+
+int capture_streams(CaptureStreams** out) {
+  static CaptureStreams cs;
+  static bool made = false;
+  if (!made) {
+    WO_TRY(hipStreamCreateWithFlags(&cs.cap, hipStreamNonBlocking));
+    for (int b = 0; b < kMaxBranches; ++b) {
+      WO_TRY(hipStreamCreateWithFlags(&cs.br[b], hipStreamNonBlocking));
+      WO_TRY(hipEventCreateWithFlags(&cs.join[b], hipEventDisableTiming));
+    }
+    WO_TRY(hipEventCreateWithFlags(&cs.fork, hipEventDisableTiming));
+    WO_TRY(hipEventCreateWithFlags(&cs.ready, hipEventDisableTiming));
+    WO_TRY(hipEventCreateWithFlags(&cs.done, hipEventDisableTiming));
+    made = true;
+  }
+  *out = &cs;
+  return WO_OK;
+}
+
+// Longest-processing-time assignment of groups to branches: groups sorted by
+// work, each placed on the least loaded branch.
+std::vector<std::vector<int>> assign_branches(const std::vector<TuneGroup>& g, int B) {
+  std::vector<int> order(g.size());
+  for (size_t k = 0; k < g.size(); ++k) order[k] = (int)k;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int a, int b) { return g[a].work > g[b].work; });
+  std::vector<std::vector<int>> br(B);
+  std::vector<double> load(B, 0.0);
+  for (int k : order) {
+    int best = 0;
+    for (int b = 1; b < B; ++b)
+      if (load[b] < load[best]) best = b;
+    br[best].push_back(k);
+    load[best] += g[k].work;
+  }
+  return br;
+}
+
+// The auto-tune of every patch (and, with f_out, the restoration), shared by
+// wo_autotune and wo_restore_tiles.
+int run_tune(wo_optics* o, int32_t n, const float* d, const double* eta,
+             const wo_autotune_opts* opts, double* loss_out, float* f_out, void* ws,
+             size_t ws_bytes, void* stream) {
+  int st = validate_thin(o, n);
+  if (st) return st;
+  if (!d || !eta || !opts || !ws) return WO_EINVAL;
+  const int starts = opts->multistart < 1 ? 1 : opts->multistart;
+  if (opts->iters < 0 || opts->use_graph < 0 || opts->use_graph > 2) return WO_EINVAL;
+  if (opts->branches < 0 || opts->branches > kMaxBranches) return WO_EINVAL;
+  for (int i = 0; i < n; ++i)
+    if (!(eta[i] > 0.0)) return WO_EINVAL;
+  size_t need = 0;
+  std::vector<TuneGroup> groups = tune_groups(o, n, starts, &need);
+  if (ws_bytes < need) return WO_ENOMEM;
+  const std::vector<size_t> doff = packed_offsets(o, n, true);
+  const std::vector<size_t> foff = packed_offsets(o, n, false);
+  hipStream_t hs = (hipStream_t)stream;
+  char* w = (char*)ws;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  for (auto& g : groups) {
+    st = tune_setup(o, g, starts, opts->theta0, d, doff.data(), eta, opts->nu_c, opts->lr, opts->lo,
+                    opts->hi, opts->tune_mask, w, hs);
+    if (st) return st;
+  }
+  const int iters = opts->iters;
+  // everything after the iterations: final loss, restoration
+  auto tail = [&](const TuneGroup& g, hipStream_t s) -> int {
+    int r = tune_iteration(g, w, starts, 0, s);
+    if (!r && f_out) r = tune_restore(g, w, starts, f_out, foff.data(), s);
+    return r;
+  };
+  if (opts->use_graph == 0 || (opts->use_graph == 1 && iters == 0)) {
+    for (int it = 0; it < iters; ++it)
+      for (auto& g : groups) {
+        st = tune_iteration(g, w, starts, 1, hs);
+        if (st) return st;
+      }
+    for (auto& g : groups) {
+      st = tail(g, hs);
+      if (st) return st;
+    }
+  } else {
+    // use_graph 1: one iteration of every group captured and replayed `iters`
+    // times; 2: the whole call (iterations, final loss, restoration) captured
+    // and launched once.  Groups run on parallel branches of the graph.
+    CaptureStreams* cs = nullptr;
+    st = capture_streams(&cs);
+    if (st) return st;
+    int B = opts->branches > 0 ? opts->branches : 4;
+    if (B > (int)groups.size()) B = (int)groups.size();
+    const std::vector<std::vector<int>> br = assign_branches(groups, B);
+    const bool was_timing = timing_enabled();
+    if (was_timing) wo_timing_enable(0);
+    WO_TRY(hipEventRecord(cs->ready, hs));
+    WO_TRY(hipStreamWaitEvent(cs->cap, cs->ready, 0));
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipError_t ce = hipStreamBeginCapture(cs->cap, hipStreamCaptureModeThreadLocal);
+    if (ce != hipSuccess) {
+      if (was_timing) wo_timing_enable(1);
+      return WO_EHIP;
+    }
+    int ist = WO_OK;
+    hipError_t fe = hipEventRecord(cs->fork, cs->cap);
+    for (int b = 0; b < B && fe == hipSuccess; ++b) fe = hipStreamWaitEvent(cs->br[b], cs->fork, 0);
+    for (int b = 0; b < B && fe == hipSuccess && !ist; ++b) {
+      for (int k : br[b]) {
+        if (opts->use_graph == 1) {
+          ist = tune_iteration(groups[k], w, starts, 1, cs->br[b]);
+        } else {
+          for (int it = 0; it < iters && !ist; ++it)
+            ist = tune_iteration(groups[k], w, starts, 1, cs->br[b]);
+          if (!ist) ist = tail(groups[k], cs->br[b]);
+        }
+        if (ist) break;
+      }
+    }
+    for (int b = 0; b < B && fe == hipSuccess; ++b) {
+      hipError_t e1 = hipEventRecord(cs->join[b], cs->br[b]);
+      hipError_t e2 = hipStreamWaitEvent(cs->cap, cs->join[b], 0);
+      if (e1 != hipSuccess) fe = e1;
+      else if (e2 != hipSuccess) fe = e2;
+    }
+    ce = hipStreamEndCapture(cs->cap, &graph);
+    if (was_timing) wo_timing_enable(1);
+    if (ist || fe != hipSuccess || ce != hipSuccess) {
+      if (graph) hipGraphDestroy(graph);
+      return ist ? ist : WO_EHIP;
+    }
+    if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+      hipGraphDestroy(graph);
+      return WO_EHIP;
+    }
+    const int launches = opts->use_graph == 1 ? iters : 1;
+    hipError_t le = hipSuccess;
+    for (int it = 0; it < launches && le == hipSuccess; ++it) le = hipGraphLaunch(exec, cs->cap);
+    hipError_t re = hipEventRecord(cs->done, cs->cap);
+    if (re == hipSuccess) re = hipStreamWaitEvent(hs, cs->done, 0);
+    hipError_t se = hipStreamSynchronize(cs->cap);
+    hipGraphExecDestroy(exec);
+    hipGraphDestroy(graph);
+    if (le != hipSuccess || re != hipSuccess || se != hipSuccess) return WO_EHIP;
+    if (opts->use_graph == 1)
+      for (auto& g : groups) {
+        st = tail(g, hs);
+        if (st) return st;
+      }
+  }
+  // read back the final state of every start; report the best one per patch
+  for (auto& g : groups) {
+    const TuneLayout& L = g.L;
+    std::vector<TuneState> h(L.nv);
+    std::vector<DevOptics> ho(L.nv);
+    WO_TRY(hipMemcpyAsync(h.data(), w + g.base + L.off_st, L.nv * sizeof(TuneState),
+                          hipMemcpyDeviceToHost, hs));
+    WO_TRY(hipMemcpyAsync(ho.data(), w + g.base + L.off_opt, L.nv * sizeof(DevOptics),
+                          hipMemcpyDeviceToHost, hs));
+    WO_TRY(hipStreamSynchronize(hs));
+    for (int j = 0; j < L.np; ++j) {
+      const int i = g.idx[j];
+      int best = j * starts;
+      for (int s2 = 1; s2 < starts; ++s2) {
+        const int v = j * starts + s2;
+        if (h[v].loss < h[best].loss) best = v;
+      }
+      o[i].defocus = ho[best].defocus;
+      o[i].na_det = ho[best].na_det;
+      o[i].tilt_zenith = ho[best].tilt_zenith;
+      o[i].tilt_azimuth = ho[best].tilt_azimuth;
+      if (loss_out) loss_out[i] = h[best].loss;
+      if (opts->all_theta_out)
+        for (int s2 = 0; s2 < starts; ++s2) {
+          const int v = j * starts + s2;
+          const long gv = (long)i * starts + s2;
+          opts->all_theta_out[4 * gv + 0] = ho[v].defocus;
+          opts->all_theta_out[4 * gv + 1] = ho[v].na_det;
+          opts->all_theta_out[4 * gv + 2] = ho[v].tilt_zenith;
+          opts->all_theta_out[4 * gv + 3] = ho[v].tilt_azimuth;
+          if (opts->all_loss_out) opts->all_loss_out[gv] = h[v].loss;
+        }
+    }
+  }
+  return WO_OK;
 }
 
 }  // namespace
@@ -643,8 +957,11 @@ extern "C" {
 
 size_t wo_tune_workspace_size(const wo_optics* o, int32_t n, int32_t starts) {
   if (!o || n < 1 || starts < 1) return 0;
-  if (o->model != WO_MODEL_LABELFREE_THIN) return 0;
-  return tune_layout(o, n, starts).total;
+  for (int i = 0; i < n; ++i)
+    if (o[i].model != WO_MODEL_LABELFREE_THIN) return 0;
+  size_t total = 0;
+  tune_groups(o, n, starts, &total);
+  return total;
 }
 
 int wo_midband_loss_grad(const wo_optics* o, int32_t n, const float* d, const double* eta,
@@ -655,21 +972,29 @@ int wo_midband_loss_grad(const wo_optics* o, int32_t n, const float* d, const do
   if (!d || !eta || !ws || !loss_out) return WO_EINVAL;
   for (int i = 0; i < n; ++i)
     if (!(eta[i] > 0.0)) return WO_EINVAL;
-  const TuneLayout L = tune_layout(o, n, 1);
-  if (ws_bytes < L.total) return WO_ENOMEM;
+  size_t need = 0;
+  std::vector<TuneGroup> groups = tune_groups(o, n, 1, &need);
+  if (ws_bytes < need) return WO_ENOMEM;
+  const std::vector<size_t> doff = packed_offsets(o, n, true);
   hipStream_t hs = (hipStream_t)stream;
   char* w = (char*)ws;
-  st = tune_setup(o, n, 1, nullptr, d, eta, nu_c, nullptr, nullptr, nullptr, 0, L, w, hs);
-  if (st) return st;
-  st = tune_iteration(o, L, w, 1, 0, hs);
-  if (st) return st;
-  std::vector<TuneState> h(n);
-  WO_TRY(hipMemcpyAsync(h.data(), w + L.off_st, n * sizeof(TuneState), hipMemcpyDeviceToHost, hs));
-  WO_TRY(hipStreamSynchronize(hs));
-  for (int i = 0; i < n; ++i) {
-    loss_out[i] = h[i].loss;
-    if (grad_out)
-      for (int j = 0; j < 4; ++j) grad_out[4 * i + j] = h[i].grad[j];
+  for (auto& g : groups) {
+    st = tune_setup(o, g, 1, nullptr, d, doff.data(), eta, nu_c, nullptr, nullptr, nullptr, 0, w, hs);
+    if (st) return st;
+    st = tune_iteration(g, w, 1, 0, hs);
+    if (st) return st;
+  }
+  for (auto& g : groups) {
+    std::vector<TuneState> h(g.L.np);
+    WO_TRY(hipMemcpyAsync(h.data(), w + g.base + g.L.off_st, g.L.np * sizeof(TuneState),
+                          hipMemcpyDeviceToHost, hs));
+    WO_TRY(hipStreamSynchronize(hs));
+    for (int j = 0; j < g.L.np; ++j) {
+      const int i = g.idx[j];
+      loss_out[i] = h[j].loss;
+      if (grad_out)
+        for (int k = 0; k < 4; ++k) grad_out[4 * i + k] = h[j].grad[k];
+    }
   }
   return WO_OK;
 }
@@ -677,90 +1002,14 @@ int wo_midband_loss_grad(const wo_optics* o, int32_t n, const float* d, const do
 int wo_autotune(wo_optics* o, int32_t n, const float* d, const double* eta,
                 const wo_autotune_opts* opts, double* loss_out, void* ws, size_t ws_bytes,
                 void* stream) {
-  int st = validate_thin(o, n);
-  if (st) return st;
-  if (!d || !eta || !opts || !ws) return WO_EINVAL;
-  const int starts = opts->multistart < 1 ? 1 : opts->multistart;
-  if (opts->iters < 0) return WO_EINVAL;
-  for (int i = 0; i < n; ++i)
-    if (!(eta[i] > 0.0)) return WO_EINVAL;
-  const TuneLayout L = tune_layout(o, n, starts);
-  if (ws_bytes < L.total) return WO_ENOMEM;
-  double lo[4], hi[4];
-  for (int j = 0; j < 4; ++j) {
-    lo[j] = opts->lo[j];
-    hi[j] = opts->hi[j];
-  }
-  clamp_box(o, lo, hi);
-  hipStream_t hs = (hipStream_t)stream;
-  char* w = (char*)ws;
-  st = tune_setup(o, n, starts, opts->theta0, d, eta, opts->nu_c, opts->lr, lo, hi,
-                  opts->tune_mask, L, w, hs);
-  if (st) return st;
-  if (opts->use_graph && opts->iters > 0) {
-    // capture one iteration on a library stream and replay it
-    static hipStream_t cap = nullptr;
-    if (!cap) WO_TRY(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
-    hipEvent_t ev0, ev1;
-    WO_TRY(hipEventCreateWithFlags(&ev0, hipEventDisableTiming));
-    WO_TRY(hipEventCreateWithFlags(&ev1, hipEventDisableTiming));
-    WO_TRY(hipEventRecord(ev0, hs));
-    WO_TRY(hipStreamWaitEvent(cap, ev0, 0));
-    const bool was_timing = timing_enabled();
-    if (was_timing) wo_timing_enable(0);
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
-    WO_TRY(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
-    const int ist = tune_iteration(o, L, w, starts, 1, cap);
-    hipError_t ce = hipStreamEndCapture(cap, &graph);
-    if (was_timing) wo_timing_enable(1);
-    if (ist) return ist;
-    WO_TRY(ce);
-    WO_TRY(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
-    for (int it = 0; it < opts->iters; ++it) WO_TRY(hipGraphLaunch(exec, cap));
-    WO_TRY(hipEventRecord(ev1, cap));
-    WO_TRY(hipStreamWaitEvent(hs, ev1, 0));
-    WO_TRY(hipStreamSynchronize(cap));
-    hipGraphExecDestroy(exec);
-    hipGraphDestroy(graph);
-    hipEventDestroy(ev0);
-    hipEventDestroy(ev1);
-  } else {
-    for (int it = 0; it < opts->iters; ++it) {
-      st = tune_iteration(o, L, w, starts, 1, hs);
-      if (st) return st;
-    }
-  }
-  // loss at the final parameters
-  st = tune_iteration(o, L, w, starts, 0, hs);
-  if (st) return st;
-  std::vector<TuneState> h(L.nv);
-  std::vector<DevOptics> ho(L.nv);
-  WO_TRY(hipMemcpyAsync(h.data(), w + L.off_st, L.nv * sizeof(TuneState), hipMemcpyDeviceToHost, hs));
-  WO_TRY(hipMemcpyAsync(ho.data(), w + L.off_opt, L.nv * sizeof(DevOptics), hipMemcpyDeviceToHost, hs));
-  WO_TRY(hipStreamSynchronize(hs));
-  for (int i = 0; i < n; ++i) {
-    int best = i * starts;
-    for (int s2 = 1; s2 < starts; ++s2) {
-      const int v = i * starts + s2;
-      if (h[v].loss < h[best].loss) best = v;
-    }
-    o[i].defocus = ho[best].defocus;
-    o[i].na_det = ho[best].na_det;
-    o[i].tilt_zenith = ho[best].tilt_zenith;
-    o[i].tilt_azimuth = ho[best].tilt_azimuth;
-    if (loss_out) loss_out[i] = h[best].loss;
-    if (opts->all_theta_out)
-      for (int s2 = 0; s2 < starts; ++s2) {
-        const int v = i * starts + s2;
-        opts->all_theta_out[4 * v + 0] = ho[v].defocus;
-        opts->all_theta_out[4 * v + 1] = ho[v].na_det;
-        opts->all_theta_out[4 * v + 2] = ho[v].tilt_zenith;
-        opts->all_theta_out[4 * v + 3] = ho[v].tilt_azimuth;
-        if (opts->all_loss_out) opts->all_loss_out[v] = h[v].loss;
-      }
-  }
-  return WO_OK;
+  return run_tune(o, n, d, eta, opts, loss_out, nullptr, ws, ws_bytes, stream);
+}
+
+int wo_restore_tiles(wo_optics* o, int32_t n, const float* d, const double* eta,
+                     const wo_autotune_opts* opts, double* loss_out, float* f_out, void* ws,
+                     size_t ws_bytes, void* stream) {
+  if (!f_out) return WO_EINVAL;
+  return run_tune(o, n, d, eta, opts, loss_out, f_out, ws, ws_bytes, stream);
 }
 
 }  // extern "C"

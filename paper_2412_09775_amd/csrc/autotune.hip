@@ -431,4 +431,29 @@ hipError_t launch_adam(DevOptics* opt, TuneState* st, const Sampling& sm, int nv
   return hipGetLastError();
 }
 
+// ------------------------------------------------------------------ best start
+
+// One thread per patch; ties keep the earliest start.
+__global__ __launch_bounds__(64) void k_pick_best(const DevOptics* __restrict__ opt,
+                                                  const TuneState* __restrict__ st, int starts,
+                                                  int npatch, DevOptics* __restrict__ ropt,
+                                                  float* __restrict__ eta) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= npatch) return;
+  const long v0 = (long)i * starts;
+  long best = v0;
+  for (int s = 1; s < starts; ++s)
+    if (st[v0 + s].loss < st[best].loss) best = v0 + s;
+  ropt[i] = opt[best];
+  eta[i] = (float)st[v0].eta;
+}
+
+hipError_t launch_pick_best(const DevOptics* opt, const TuneState* st, int starts, int npatch,
+                            DevOptics* ropt, float* eta, hipStream_t s) {
+  { ScopedTiming _t("k_pick_best", s);
+  hipLaunchKernelGGL(k_pick_best, dim3((unsigned)((npatch + 63) / 64)), dim3(64), 0, s, opt, st, starts,
+                     npatch, ropt, eta); }
+  return hipGetLastError();
+}
+
 }  // namespace wo

@@ -700,6 +700,25 @@ __global__ void k_add_noise(float* __restrict__ x, long n, float sigma, unsigned
   x[i] += sigma * (float)(r * cos(2.0 * M_PI * u01(h2)));
 }
 
+// One thread per output voxel: the window of each stack at (z0, y0, x0),
+// zero outside the input and outside the central keep[i] planes.
+__global__ void k_crop(const float* __restrict__ in, int nz, int ny, int nx, float* out, int oz,
+                       int oy, int ox, int z0, int y0, int x0, const int* __restrict__ keep,
+                       long total) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= total) return;
+  const int x = (int)(e % ox);
+  const long r = e / ox;
+  const int y = (int)(r % oy);
+  const long r2 = r / oy;
+  const int z = (int)(r2 % oz);
+  const long i = r2 / oz;
+  const int zi = z + z0, yi = y + y0, xi = x + x0;
+  bool in_win = zi >= 0 && zi < nz && yi >= 0 && yi < ny && xi >= 0 && xi < nx;
+  if (keep) in_win = in_win && abs(2 * z - (oz - 1)) < keep[i];
+  out[e] = in_win ? in[((i * nz + zi) * (long)ny + yi) * nx + xi] : 0.f;
+}
+
 }  // namespace wo
 
 // ------------------------------------------------------------------ C ABI
@@ -723,6 +742,19 @@ int wo_add_gaussian_noise(float* x, int64_t n, double sigma, uint64_t seed, void
   if (n == 0) return WO_OK;
   hipLaunchKernelGGL(wo::k_add_noise, dim3(wo::blocks(n, 256)), dim3(256), 0, (hipStream_t)stream, x,
                      (long)n, (float)sigma, (unsigned long long)seed);
+  WO_HIP_CHECK(hipGetLastError());
+  return WO_OK;
+}
+
+int wo_crop_stacks(const float* in, int32_t n, int32_t nz, int32_t ny, int32_t nx, float* out,
+                   int32_t oz, int32_t oy, int32_t ox, int32_t z0, int32_t y0, int32_t x0,
+                   const int32_t* keep_z, void* stream) {
+  if (!in || !out || n < 1 || nz < 1 || ny < 1 || nx < 1 || oz < 1 || oy < 1 || ox < 1)
+    return WO_EINVAL;
+  if (in == out && (nz != oz || ny != oy || nx != ox || z0 || y0 || x0)) return WO_EALIAS;
+  const long total = (long)n * oz * oy * ox;
+  hipLaunchKernelGGL(wo::k_crop, dim3(wo::blocks(total, 256)), dim3(256), 0, (hipStream_t)stream, in,
+                     nz, ny, nx, out, oz, oy, ox, z0, y0, x0, keep_z, total);
   WO_HIP_CHECK(hipGetLastError());
   return WO_OK;
 }

@@ -509,10 +509,12 @@ __global__ __launch_bounds__(256) void k_op2d(float2* __restrict__ spec,
                                               const float2* __restrict__ tf, int C, long M,
                                               int slots, int mode, float eta,
                                               const float* __restrict__ bg, float inv_n,
-                                              float n_full, long blocks_per_patch) {
+                                              float n_full, long blocks_per_patch,
+                                              const float* __restrict__ eta_pp) {
   const long patch = blockIdx.x / blocks_per_patch;
   const long m = (blockIdx.x - patch * blocks_per_patch) * (long)blockDim.x + threadIdx.x;
   if (m >= M) return;
+  if (eta_pp) eta = eta_pp[patch];
   float2* sp = spec + patch * (long)slots * M;
   const float2* tp = tf + patch * (long)C * P * M;
   const float* bp = bg ? bg + patch * C : nullptr;
@@ -523,7 +525,7 @@ __global__ __launch_bounds__(256) void k_op2d(float2* __restrict__ spec,
 
 hipError_t launch_op2d(float2* spec, const float2* tf, int C, int P, long M, int slots, int npatch,
                        int mode, float eta, const float* bg, float inv_n, double n_full,
-                       hipStream_t s) {
+                       hipStream_t s, const float* eta_pp) {
   const long bpp = (M + 255) / 256;
   const long nwg = bpp * npatch;
   const float nf = (float)n_full;
@@ -531,17 +533,17 @@ hipError_t launch_op2d(float2* spec, const float2* tf, int C, int P, long M, int
     case 1:
       { ScopedTiming _t("k_op2d<1>", s);
       hipLaunchKernelGGL(k_op2d<1>, dim3((unsigned)nwg), dim3(256), 0, s, spec, tf, C, M, slots,
-                         mode, eta, bg, inv_n, nf, bpp); }
+                         mode, eta, bg, inv_n, nf, bpp, eta_pp); }
       break;
     case 2:
       { ScopedTiming _t("k_op2d<2>", s);
       hipLaunchKernelGGL(k_op2d<2>, dim3((unsigned)nwg), dim3(256), 0, s, spec, tf, C, M, slots,
-                         mode, eta, bg, inv_n, nf, bpp); }
+                         mode, eta, bg, inv_n, nf, bpp, eta_pp); }
       break;
     case 4:
       { ScopedTiming _t("k_op2d<4>", s);
       hipLaunchKernelGGL(k_op2d<4>, dim3((unsigned)nwg), dim3(256), 0, s, spec, tf, C, M, slots,
-                         mode, eta, bg, inv_n, nf, bpp); }
+                         mode, eta, bg, inv_n, nf, bpp, eta_pp); }
       break;
     default:
       return hipErrorInvalidValue;

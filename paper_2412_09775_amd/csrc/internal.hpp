@@ -65,9 +65,10 @@ hipError_t launch_zop(float2* spec, const float2* tf, int C, int P, int Z, long 
                       int npatch, int mode, float eta, const float* bg, float inv_n, double n_full,
                       hipStream_t s);
 // 2D (thin) per-frequency op: spec [slots][M] per patch, tf [C][P][M] per patch.
+// eta_pp (device [npatch], may be NULL) overrides eta per patch.
 hipError_t launch_op2d(float2* spec, const float2* tf, int C, int P, long M, int slots, int npatch,
                        int mode, float eta, const float* bg, float inv_n, double n_full,
-                       hipStream_t s);
+                       hipStream_t s, const float* eta_pp = nullptr);
 
 // Transfer-function synthesis.
 hipError_t launch_set_params(DevOptics* dst, const DevOptics* host, int n, hipStream_t s);
@@ -98,5 +99,9 @@ hipError_t launch_tf_grad_y(const DevOptics* opt, const Sampling& sm, int nv, co
 hipError_t launch_adam(DevOptics* opt, TuneState* st, const Sampling& sm, int nv,
                        const double* ppart, const double* lpart, const double* dpart,
                        const double* gpart, const double* ipart, int update, hipStream_t s);
+// Per patch, the start with the lowest loss: its optics into ropt[i] and the
+// patch's eta into eta[i].
+hipError_t launch_pick_best(const DevOptics* opt, const TuneState* st, int starts, int npatch,
+                            DevOptics* ropt, float* eta, hipStream_t s);
 
 }  // namespace wo

@@ -71,6 +71,33 @@ def simulate(template, n, seed, device, noise_sigma=0.03, chunk=1024, ncells=8, 
     return stacks, theta
 
 
+def clear_outer_planes(stacks, seed, keeps=(16, 24, 32)):
+    """In place: each stack keeps only its central k planes, k drawn uniformly from
+    `keeps`, so that the network also learns from the zero-padded inputs of tiles
+    with fewer planes (see ``network_input``)."""
+    rng = np.random.default_rng(seed)
+    keep = rng.choice(np.asarray(keeps), stacks.shape[0]).astype(np.int32)
+    api.crop_stacks(stacks, tuple(stacks.shape[1:]), keep_z=keep, out=stacks)
+    return keep
+
+
+def network_input(tiles, shape=(32, 64, 64), out=None):
+    """The centred (Z, Y, X) = `shape` window of each tile (a list of (Z_i, Y_i, X_i)
+    device stacks of any size): central planes of deeper tiles, symmetric zero
+    padding of shallower ones.  Returns (n, *shape)."""
+    import torch
+    oz, oy, ox = shape
+    n = len(tiles)
+    if out is None:
+        out = torch.empty((n, oz, oy, ox), dtype=torch.float32, device=tiles[0].device)
+    for i, t in enumerate(tiles):
+        Z, Y, X = t.shape
+        # centre plane of the window (oz - 1) / 2 on the tile's centre (Z - 1) / 2
+        api.crop_stacks(t.reshape(1, Z, Y, X), shape, ((Z - oz) // 2, (Y - oy) // 2, (X - ox) // 2),
+                        out=out[i:i + 1])
+    return out
+
+
 class LearnedInit:
     """FP32 master parameters and AdamW moments on the device."""
 

@@ -128,3 +128,30 @@ def test_training_reduces_the_loss(gpu_lib):
     torch.cuda.synchronize()
     print(f"  epoch losses {hist}")
     assert hist[-1] < 0.7 * hist[0]
+
+
+@pytest.mark.parametrize("Z", [16, 24, 32, 48])
+def test_network_input_window(gpu_lib, Z):
+    """Centred 32x64x64 window of a tile: central planes or symmetric zero padding,
+    the same planes a 32-plane stack with its outer planes cleared keeps."""
+    import torch
+    from paper_2412_09775_amd import learned_init
+    rng = np.random.default_rng(Z)
+    t = rng.standard_normal((Z, 96, 80)).astype(np.float32)
+    got = learned_init.network_input([torch.from_numpy(t).cuda()]).cpu().numpy()[0]
+    ref = np.zeros((32, 64, 64), np.float32)
+    z0 = (Z - 32) // 2
+    for z in range(32):
+        if 0 <= z + z0 < Z:
+            ref[z] = t[z + z0, 16:80, 8:72]
+    assert np.array_equal(got, ref)
+    full = rng.standard_normal((2, 32, 8, 8)).astype(np.float32)
+    x = torch.from_numpy(full).cuda()
+    keep = np.array([Z if Z <= 32 else 32, 32], np.int32)
+    gpu_lib.crop_stacks(x, (32, 8, 8), keep_z=keep, out=x)
+    kept = x.cpu().numpy()
+    for i in range(2):
+        lo = (32 - keep[i]) // 2
+        ref = np.zeros_like(full[i])
+        ref[lo:lo + keep[i]] = full[i, lo:lo + keep[i]]
+        assert np.array_equal(kept[i], ref)
