@@ -103,6 +103,9 @@ def main():
     ap.add_argument("--cnn-epochs", type=int, default=8)
     ap.add_argument("--cnn-tune-iters", type=int, default=20)
     ap.add_argument("--restore-tiles", type=int, default=64)
+    ap.add_argument("--no-fft-tune", action="store_true", help="keep the default FFT schedules")
+    ap.add_argument("--fft-plans", default="", help="import an FFT schedule table instead of tuning")
+    ap.add_argument("--save-fft-plans", default="", help="write the FFT schedule table used")
     ap.add_argument("--restore-graph", type=int, default=1, choices=(0, 1, 2))
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for HBM counters)")
@@ -161,6 +164,32 @@ def main():
     torch.cuda.synchronize()
     print("[bench] warmup done", file=sys.stderr, flush=True)
 
+    # ---- FFT schedules: the library's defaults, then the tuner's picks (or a saved table)
+    tuner = {}
+    if args.fft_plans:
+        api.fft_plans_import(open(args.fft_plans).read())
+        tuner["imported"] = os.path.basename(args.fft_plans)
+    elif not args.no_fft_tune:
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        for _ in range(args.steps):
+            full_step()
+        torch.cuda.synchronize()
+        tuner["ms_per_step_default_schedules"] = (time.perf_counter() - a) * 1e3 / args.steps
+        a = time.perf_counter()
+        api.fft_tune(api.OP_TRANSFER_FUNCTION, [o], out=tf_buf, ws=ws_tf, stream=stream)
+        api.fft_tune(api.OP_RECONSTRUCT, [o], tf=tf_buf, x=d, out=fout, eta=eta, ws=ws_rec, stream=stream)
+        tuner["tune_s"] = round(time.perf_counter() - a, 3)
+        for _ in range(args.warmup):
+            full_step()
+        torch.cuda.synchronize()
+    if args.save_fft_plans:
+        os.makedirs(os.path.dirname(os.path.abspath(args.save_fft_plans)), exist_ok=True)
+        with open(args.save_fft_plans, "w") as fh:
+            fh.write(api.fft_plans_export())
+    tuner["table"] = api.fft_plans_export().splitlines()
+    print(f"[bench] fft schedules: {tuner}", file=sys.stderr, flush=True)
+
     # ---- timed region: K whole steps, with per-kernel HIP events on the library's stream
     api.timing_enable(True)
     torch.cuda.synchronize()
@@ -215,6 +244,7 @@ def main():
         "config": {"workload": "label-free 3D phase+absorption, 96x512x512, 1 channel x 2 properties",
                    "shape_zyx": [Z, Y, X], "voxel_um": [o.dz, o.dy, o.dx], "eta_rel": ETA_REL},
         "reconstruct_cached_tf": {"ms": ms_rec, "voxels_per_s": V / (ms_rec * 1e-3)},
+        "fft_schedules": tuner,
         "roofline": roof,
         "kernels": kernels,
     }

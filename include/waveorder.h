@@ -211,6 +211,41 @@ int wo_restore_tiles(wo_optics* o, int32_t n, const float* d, const double* eta,
                      const wo_autotune_opts* opts, double* loss_out, float* f_out, void* ws,
                      size_t ws_bytes, void* stream);
 
+/* ---------------------------------------------------------------- FFT schedule tuner
+ * Not in the paper (its transforms are library calls).  Every FFT pass of the
+ * library -- rows along X (real <-> half spectrum), strided columns along Y
+ * (and Z for the transfer functions), and the Z pass fused with the
+ * per-frequency operator -- is launched with a schedule: the lines or columns
+ * one workgroup transforms, the workgroup size, and the radix plan (compiled
+ * stages for the compiled lengths, else a runtime plan in one of three radix
+ * orders).  Without tuning each pass takes a fixed heuristic schedule; a
+ * process-wide table keyed by (pass, length, columns, batch[, P, C, mode])
+ * overrides it.  Tuning or importing changes launch schedules only: results
+ * are the same transform up to FP32 rounding.  The table is guarded by a
+ * mutex; tuning while other threads launch work on the same device distorts
+ * its timings. */
+
+/* Runs one call -- op WO_OP_TRANSFER_FUNCTION (writes `out` as tf_out),
+ * WO_OP_FORWARD (in = f, out = d), WO_OP_RECONSTRUCT (in = d, out = f, eta)
+ * or WO_OP_ADJOINT (in = r, out = g), arguments as for that call, b = NULL --
+ * while recording its tunable passes, then times every candidate schedule of
+ * each pass `reps` times on the call's own buffers and stores the fastest.
+ * On return `out` and `ws` hold unspecified values (run the call again);
+ * tf and in are only read.  Synchronises `stream`. */
+int wo_fft_tune(int32_t op, const wo_optics* o, int32_t n, const void* tf, const float* in, float* out,
+                double eta, int32_t reps, void* ws, size_t ws_bytes, void* stream);
+/* The table as text, one line "kind n m batch extra w threads plan" per entry
+ * (kind: rows_r2c, rows_c2r, cols, zop); NUL-terminated, truncated to len;
+ * *needed (may be NULL) receives the full size including the NUL. */
+int wo_fft_plans_export(char* buf, size_t len, size_t* needed);
+/* Adds entries in the export format; all or none: WO_EINVAL if a line is
+ * malformed or names a schedule the pass does not accept on this device. */
+int wo_fft_plans_import(const char* text);
+int wo_fft_plans_clear(void);
+/* Every schedule the pass "kind n m batch extra" accepts on this device, in
+ * the export format (the first line is the default schedule). */
+int wo_fft_candidates(const char* key_line, char* buf, size_t len, size_t* needed);
+
 /* ---------------------------------------------------------------- learned initialiser
  * Not in the paper: a small 3D CNN that regresses normalised (defocus, NA_det,
  * tilt_zenith) from a defocus stack, used to start the auto-tune.  4 blocks of

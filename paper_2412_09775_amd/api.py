@@ -35,7 +35,8 @@ SYMBOLS = ("wo_bank_shape", "wo_workspace_size", "wo_transfer_function", "wo_for
            "wo_restore_tiles",
            "wo_cnn_param_count", "wo_cnn_workspace_size", "wo_cnn_forward", "wo_cnn_gradient",
            "wo_cnn_train_step", "wo_conv3d_forward", "wo_conv3d_input_grad", "wo_conv3d_weight_grad",
-           "wo_synth_thin_cells", "wo_add_gaussian_noise", "wo_crop_stacks")
+           "wo_synth_thin_cells", "wo_add_gaussian_noise", "wo_crop_stacks", "wo_fft_tune",
+           "wo_fft_plans_export", "wo_fft_plans_import", "wo_fft_plans_clear", "wo_fft_candidates")
 
 _FIELDS = ("model", "nz", "ny", "nx", "dz", "dy", "dx", "wavelength", "na_ill", "na_det",
            "n_medium", "defocus", "tilt_zenith", "tilt_azimuth", "edge_width", "swing")
@@ -129,6 +130,11 @@ def load(path: str = LIB_PATH):
     lib.wo_conv3d_weight_grad.argtypes = conv + [vp, sz, vp]
     lib.wo_synth_thin_cells.argtypes = [vp, i32, i32, i32, f64, i32, u64, vp]
     lib.wo_add_gaussian_noise.argtypes = [vp, i64, f64, u64, vp]
+    szp = ctypes.POINTER(ctypes.c_size_t)
+    lib.wo_fft_tune.argtypes = [i32, op, i32, vp, vp, vp, f64, i32, vp, sz, vp]
+    lib.wo_fft_plans_export.argtypes = [ctypes.c_char_p, sz, szp]
+    lib.wo_fft_plans_import.argtypes = [ctypes.c_char_p]
+    lib.wo_fft_candidates.argtypes = [ctypes.c_char_p, ctypes.c_char_p, sz, szp]
     lib.wo_crop_stacks.argtypes = [vp, i32, i32, i32, i32, vp, i32, i32, i32, i32, i32, i32, vp, vp]
     lib.wo_timing_enable.argtypes = [ctypes.c_int]
     lib.wo_timing_report.argtypes = [ctypes.c_char_p, ctypes.c_size_t]
@@ -566,3 +572,42 @@ def crop_stacks(x, out_shape, offsets=(0, 0, 0), keep_z=None, out=None, stream=N
     _check(load().wo_crop_stacks(_ptr(x), n, Z, Y, X, _ptr(out), oz, oy, ox, *[int(v) for v in offsets],
                                  _ptr(keep), _stream(stream)), "wo_crop_stacks")
     return out
+
+
+# ---------------------------------------------------------------- FFT schedule tuner
+
+def fft_tune(op, optics, tf=None, x=None, out=None, eta=0.0, reps=3, ws=None, stream=None):
+    """Time every candidate schedule of the FFT passes of one call (see ``wo_fft_tune``)
+    and keep the fastest; `out` and `ws` hold unspecified values afterwards."""
+    import torch
+    lib = load()
+    arr = optics_array(optics)
+    dev = out.device
+    ws, _ = _workspace(optics, op, dev, ws)
+    _check(lib.wo_fft_tune(int(op), arr, len(arr), _ptr(tf), _ptr(x), _ptr(out), float(eta), int(reps),
+                           _ptr(ws), ws.numel(), _stream(stream)), "wo_fft_tune")
+
+
+def _text_call(fn, *args):
+    need = ctypes.c_size_t(0)
+    _check(fn(*args, None, 0, ctypes.byref(need)), fn.__name__)
+    buf = ctypes.create_string_buffer(need.value)
+    _check(fn(*args, buf, need.value, None), fn.__name__)
+    return buf.value.decode()
+
+
+def fft_plans_export() -> str:
+    return _text_call(load().wo_fft_plans_export)
+
+
+def fft_plans_import(text: str):
+    _check(load().wo_fft_plans_import(text.encode()), "wo_fft_plans_import")
+
+
+def fft_plans_clear():
+    _check(load().wo_fft_plans_clear(), "wo_fft_plans_clear")
+
+
+def fft_candidates(key_line: str) -> list:
+    """Schedules (export-format lines) the pass "kind n m batch extra" accepts."""
+    return [ln for ln in _text_call(load().wo_fft_candidates, key_line.encode()).splitlines() if ln]

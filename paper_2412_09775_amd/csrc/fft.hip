@@ -106,28 +106,67 @@ static int lines_per_wg_for(int X) {
   return L;
 }
 
+// Lengths with compiled stages.
+static bool compiled_length(int n) {
+  switch (n) {
+#define X_(NN) case NN:
+    WO_ALL_SIZES(X_)
+#undef X_
+    return true;
+    default:
+      return false;
+  }
+}
+
+static bool threads_ok(int thr, long elems) {
+  return thr >= 64 && thr <= kMaxThreads && thr % 64 == 0 && (long)thr * kEmax >= elems;
+}
+
+static bool rows_choice_ok(int X, const FftChoice& c) {
+  const long elems = (long)c.w * X;
+  return c.w >= 1 && c.w <= 64 && elems <= kMaxElems && threads_ok(c.threads, elems) &&
+         (long)(X + elems) * (long)sizeof(float2) <= lds_limit_bytes() && c.plan >= 0 && c.plan <= 3;
+}
+
+static FftChoice rows_default(int X) {
+  const int L = lines_per_wg_for(X);
+  return FftChoice{L, threads_for((long)L * X), 0};
+}
+
+// Table entry for the launch, or the default; an entry the device cannot run
+// falls back to the default.
+static FftChoice rows_choice(const FftKey& k) {
+  FftChoice c;
+  if (fft_lookup(k, &c) && rows_choice_ok(k.n, c)) return c;
+  return rows_default(k.n);
+}
+
 #define WO_CASE_ROWS(K, NN)                                                                      \
   case NN:                                                                                       \
     hipLaunchKernelGGL((K<NN>), dim3((unsigned)nwg), dim3(thr), lds, s, WO_ROWS_ARGS);          \
-    break;
+    return hipGetLastError();
 
 hipError_t launch_rows_r2c(const float* in, float2* out, int X, const RowGroups& g, hipStream_t s) {
-  FftPlan plan;
-  if (!make_plan(X, &plan)) return hipErrorInvalidValue;
   const long nrows = g.rows_per_group * g.ngroups;
+  const FftKey key{kFftRowsR2C, X, 0, nrows, 0};
+  if (fft_recording()) fft_record(key, [=] { return launch_rows_r2c(in, out, X, g, s); });
+  const FftChoice c = rows_choice(key);
+  FftPlan plan;
+  if (!make_plan_variant(X, c.plan, &plan)) return hipErrorInvalidValue;
   const long nlines = (nrows + 1) / 2;
-  const int L = lines_per_wg_for(X);
+  const int L = c.w;
   const long nwg = (nlines + L - 1) / L;
-  const int thr = threads_for((long)L * X);
+  const int thr = c.threads;
   const size_t lds = (size_t)(X + L * X) * sizeof(float2);
   ScopedTiming _t("k_rows_r2c", s);
 #define WO_ROWS_ARGS in, out, X, g, plan, L, nlines
 #define X_(NN) WO_CASE_ROWS(k_rows_r2c, NN)
-  switch (X) {
-    WO_LATERAL_SIZES(X_)
-    default:
-      hipLaunchKernelGGL((k_rows_r2c<0>), dim3((unsigned)nwg), dim3(thr), lds, s, WO_ROWS_ARGS);
-  }
+  if (c.plan == 0) switch (X) {
+      WO_LATERAL_SIZES(X_)
+      default:
+        break;
+    }
+  hipLaunchKernelGGL((k_rows_r2c<0>), dim3((unsigned)nwg), dim3(thr), lds, s, WO_ROWS_ARGS);
 #undef X_
 #undef WO_ROWS_ARGS
   return hipGetLastError();
@@ -135,22 +174,26 @@ hipError_t launch_rows_r2c(const float* in, float2* out, int X, const RowGroups&
 
 hipError_t launch_rows_c2r(const float2* in, float* out, int X, const RowGroups& g, float scale,
                            hipStream_t s) {
-  FftPlan plan;
-  if (!make_plan(X, &plan)) return hipErrorInvalidValue;
   const long nrows = g.rows_per_group * g.ngroups;
+  const FftKey key{kFftRowsC2R, X, 0, nrows, 0};
+  if (fft_recording()) fft_record(key, [=] { return launch_rows_c2r(in, out, X, g, scale, s); });
+  const FftChoice c = rows_choice(key);
+  FftPlan plan;
+  if (!make_plan_variant(X, c.plan, &plan)) return hipErrorInvalidValue;
   const long nlines = (nrows + 1) / 2;
-  const int L = lines_per_wg_for(X);
+  const int L = c.w;
   const long nwg = (nlines + L - 1) / L;
-  const int thr = threads_for((long)L * X);
+  const int thr = c.threads;
   const size_t lds = (size_t)(X + L * X) * sizeof(float2);
   ScopedTiming _t("k_rows_c2r", s);
 #define WO_ROWS_ARGS in, out, X, g, plan, L, nlines, scale
 #define X_(NN) WO_CASE_ROWS(k_rows_c2r, NN)
-  switch (X) {
-    WO_LATERAL_SIZES(X_)
-    default:
-      hipLaunchKernelGGL((k_rows_c2r<0>), dim3((unsigned)nwg), dim3(thr), lds, s, WO_ROWS_ARGS);
-  }
+  if (c.plan == 0) switch (X) {
+      WO_LATERAL_SIZES(X_)
+      default:
+        break;
+    }
+  hipLaunchKernelGGL((k_rows_c2r<0>), dim3((unsigned)nwg), dim3(thr), lds, s, WO_ROWS_ARGS);
 #undef X_
 #undef WO_ROWS_ARGS
   return hipGetLastError();
@@ -204,33 +247,52 @@ constexpr int static_tile_width(int n) {
   return W;
 }
 
+static bool cols_choice_ok(int N, const FftChoice& c) {
+  const long elems = (long)c.w * N;
+  return c.w >= 1 && c.w <= 64 && elems <= kMaxElems && threads_ok(c.threads, elems) &&
+         (long)(N + elems) * (long)sizeof(float2) <= lds_limit_bytes() && c.plan >= 0 && c.plan <= 3;
+}
+
+static FftChoice cols_default(int N) {
+  const int W = compiled_length(N) && (long)(N + static_tile_width(N) * N) * (long)sizeof(float2) <=
+                                          lds_limit_bytes()
+                    ? static_tile_width(N)
+                    : tile_width(N, 1);
+  return FftChoice{W, threads_for((long)N * W), 0};
+}
+
 hipError_t launch_cols(float2* data, int N, long M, long planes_per_group, long group_stride,
                        long ngroups, float sign, hipStream_t s, const char* tag) {
+  const FftKey key{kFftCols, N, M, planes_per_group * ngroups, 0};
+  if (fft_recording())
+    fft_record(key, [=] {
+      return launch_cols(data, N, M, planes_per_group, group_stride, ngroups, sign, s, tag);
+    });
+  FftChoice c;
+  if (!fft_lookup(key, &c) || !cols_choice_ok(N, c)) c = cols_default(N);
   FftPlan plan;
-  if (!make_plan(N, &plan)) return hipErrorInvalidValue;
-  int W = tile_width(N, 1);
+  if (!make_plan_variant(N, c.plan, &plan)) return hipErrorInvalidValue;
+  const int W = c.w;
+  const long tiles = (M + W - 1) / W;
+  const long nwg = tiles * planes_per_group * ngroups;
+  const int thr = c.threads;
+  const size_t lds = (size_t)(N + N * W) * sizeof(float2);
   ScopedTiming _t(tag, s);
 #define X_(NN)                                                                                  \
   case NN:                                                                                      \
-    if ((long)(NN + static_tile_width(NN) * NN) * (long)sizeof(float2) <= lds_limit_bytes()) {   \
-      constexpr int WS = static_tile_width(NN);                                                 \
-      const long tiles = (M + WS - 1) / WS;                                                     \
-      hipLaunchKernelGGL((k_cols<NN, WS>), dim3((unsigned)(tiles * planes_per_group * ngroups)), \
-                         dim3(threads_for((long)NN * WS)), (size_t)(NN + NN * WS) * sizeof(float2), s, \
-                         data, N, M, WS, tiles, planes_per_group, group_stride, plan, sign);     \
-      return hipGetLastError();                                                                 \
-    }                                                                                           \
-    break;
-  switch (N) {
-    WO_ALL_SIZES(X_)
-    default:
-      break;
-  }
+    if (W == static_tile_width(NN))                                                             \
+      hipLaunchKernelGGL((k_cols<NN, static_tile_width(NN)>), dim3((unsigned)nwg), dim3(thr), lds, \
+                         s, data, N, M, W, tiles, planes_per_group, group_stride, plan, sign);  \
+    else                                                                                        \
+      hipLaunchKernelGGL((k_cols<NN, 0>), dim3((unsigned)nwg), dim3(thr), lds, s, data, N, M, W, \
+                         tiles, planes_per_group, group_stride, plan, sign);                    \
+    return hipGetLastError();
+  if (c.plan == 0) switch (N) {
+      WO_ALL_SIZES(X_)
+      default:
+        break;
+    }
 #undef X_
-  const long tiles = (M + W - 1) / W;
-  const long nwg = tiles * planes_per_group * ngroups;
-  const int thr = threads_for((long)N * W);
-  const size_t lds = (size_t)(N + N * W) * sizeof(float2);
   hipLaunchKernelGGL((k_cols<0, 0>), dim3((unsigned)nwg), dim3(thr), lds, s, data, N, M, W, tiles,
                      planes_per_group, group_stride, plan, sign);
   return hipGetLastError();
@@ -461,47 +523,146 @@ __global__ __launch_bounds__(1024) void k_zop(float2* __restrict__ spec,
 }
 
 template <int P, int CT>
-static void zop_launch(long nwg, int thr, size_t lds, hipStream_t s, float2* spec, const float2* tf,
-                       int C, int Z, long M, int slots, int W, long tiles, FftPlan plan, int mode,
-                       float eta, const float* bg, float inv_n, float nf) {
+static void zop_launch(bool use_static, long nwg, int thr, size_t lds, hipStream_t s, float2* spec,
+                       const float2* tf, int C, int Z, long M, int slots, int W, long tiles,
+                       FftPlan plan, int mode, float eta, const float* bg, float inv_n, float nf) {
 #define X_(NN)                                                                                   \
   case NN:                                                                                       \
     hipLaunchKernelGGL((k_zop<P, CT, NN>), dim3((unsigned)nwg), dim3(thr), lds, s, spec, tf, C, Z, M, \
                        slots, W, tiles, plan, mode, eta, bg, inv_n, nf);                         \
     return;
-  switch (Z) {
-    WO_AXIAL_SIZES(X_)
-    default:
-      break;
-  }
+  if (use_static) switch (Z) {
+      WO_AXIAL_SIZES(X_)
+      default:
+        break;
+    }
 #undef X_
   hipLaunchKernelGGL((k_zop<P, CT, 0>), dim3((unsigned)nwg), dim3(thr), lds, s, spec, tf, C, Z, M,
                      slots, W, tiles, plan, mode, eta, bg, inv_n, nf);
 }
 
+static bool zop_choice_ok(int Z, int CH, const FftChoice& c) {
+  const long elems = (long)c.w * Z * CH;
+  return c.w >= 1 && c.w <= 64 && elems <= kMaxElems && threads_ok(c.threads, elems) &&
+         (long)(Z + elems) * (long)sizeof(float2) <= lds_limit_bytes() && c.plan >= 0 && c.plan <= 3;
+}
+
+static FftChoice zop_default(int Z, int CH) {
+  const int W = tile_width(Z, CH);
+  return FftChoice{W, threads_for((long)CH * Z * W), 0};
+}
+
 hipError_t launch_zop(float2* spec, const float2* tf, int C, int P, int Z, long M, int slots,
                       int npatch, int mode, float eta, const float* bg, float inv_n, double n_full,
                       hipStream_t s) {
-  FftPlan plan;
-  if (!make_plan(Z, &plan)) return hipErrorInvalidValue;
+  const FftKey key{kFftZop, Z, M, npatch, P * 1000 + C * 10 + mode};
+  if (fft_recording())
+    fft_record(key, [=] {
+      return launch_zop(spec, tf, C, P, Z, M, slots, npatch, mode, eta, bg, inv_n, n_full, s);
+    });
   const int cin = mode == kModeForward ? P : C;
   const int cout = mode == kModeForward ? C : P;
   const int CH = cin > cout ? cin : cout;
-  const int W = tile_width(Z, CH);
+  FftChoice c;
+  if (!fft_lookup(key, &c) || !zop_choice_ok(Z, CH, c)) c = zop_default(Z, CH);
+  FftPlan plan;
+  if (!make_plan_variant(Z, c.plan, &plan)) return hipErrorInvalidValue;
+  const int W = c.w;
   const long tiles = (M + W - 1) / W;
   const long nwg = tiles * npatch;
-  const int thr = threads_for((long)CH * Z * W);
+  const int thr = c.threads;
   const size_t lds = (size_t)(Z + CH * Z * W) * sizeof(float2);
   const float nf = (float)n_full;
+  const bool st = c.plan == 0;
   ScopedTiming _t(P == 1 ? "k_zop<1>" : (P == 2 ? "k_zop<2>" : "k_zop<4>"), s);
 #define WO_ZOP(PP, CC) \
-  zop_launch<PP, CC>(nwg, thr, lds, s, spec, tf, C, Z, M, slots, W, tiles, plan, mode, eta, bg, inv_n, nf)
+  zop_launch<PP, CC>(st, nwg, thr, lds, s, spec, tf, C, Z, M, slots, W, tiles, plan, mode, eta, bg, inv_n, nf)
   if (P == 1) { if (C == 1) WO_ZOP(1, 1); else WO_ZOP(1, 0); }
   else if (P == 2) { if (C == 1) WO_ZOP(2, 1); else WO_ZOP(2, 0); }
   else if (P == 4) { if (C == 1) WO_ZOP(4, 1); else WO_ZOP(4, 0); }
   else return hipErrorInvalidValue;
 #undef WO_ZOP
   return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ schedule candidates
+
+static std::vector<int> thread_options(long elems) {
+  std::vector<int> t;
+  for (int per : {kEmax, kEmax / 2, kEmax / 4}) {
+    long thr = (elems + per - 1) / per;
+    thr = ((thr + 63) / 64) * 64;
+    if (thr < 64) thr = 64;
+    if (thr > kMaxThreads) continue;
+    bool seen = false;
+    for (int x : t) seen |= x == (int)thr;
+    if (!seen) t.push_back((int)thr);
+  }
+  return t;
+}
+
+// Radix-plan variants of n whose pass sequences differ from each other (and,
+// for compiled lengths, runtime plans other than the default order).
+static std::vector<int> plan_options(int n) {
+  std::vector<int> v{0};
+  FftPlan p0, p;
+  if (!make_plan_variant(n, 1, &p0)) return v;
+  std::vector<unsigned long long> seen{p0.radices};
+  for (int var : {2, 3}) {
+    if (!make_plan_variant(n, var, &p)) continue;
+    bool dup = false;
+    for (auto r : seen) dup |= r == p.radices;
+    if (!dup) {
+      v.push_back(var);
+      seen.push_back(p.radices);
+    }
+  }
+  return v;
+}
+
+std::vector<FftChoice> fft_candidates(const FftKey& k) {
+  std::vector<FftChoice> out;
+  auto add = [&](const FftChoice& c) {
+    for (auto& x : out)
+      if (x.w == c.w && x.threads == c.threads && x.plan == c.plan) return;
+    out.push_back(c);
+  };
+  std::vector<int> widths{1, 2, 4, 8, 16, 32, 64};
+  const std::vector<int> plans = plan_options(k.n);
+  if (k.kind == kFftRowsR2C || k.kind == kFftRowsC2R) {
+    const FftChoice d = rows_default(k.n);
+    add(d);
+    widths.push_back(d.w);
+    for (int pl : plans)
+      for (int w : widths)
+        for (int t : thread_options((long)w * k.n)) {
+          const FftChoice c{w, t, pl};
+          if (rows_choice_ok(k.n, c)) add(c);
+        }
+  } else if (k.kind == kFftCols) {
+    const FftChoice d = cols_default(k.n);
+    add(d);
+    for (int pl : plans)
+      for (int w : widths)
+        for (int t : thread_options((long)w * k.n)) {
+          const FftChoice c{w, t, pl};
+          if (cols_choice_ok(k.n, c)) add(c);
+        }
+  } else if (k.kind == kFftZop) {
+    const int P = k.extra / 1000, C = (k.extra / 10) % 100, mode = k.extra % 10;
+    const int cin = mode == kModeForward ? P : C;
+    const int cout = mode == kModeForward ? C : P;
+    const int CH = cin > cout ? cin : cout;
+    const FftChoice d = zop_default(k.n, CH);
+    add(d);
+    for (int pl : plans)
+      for (int w : widths)
+        for (int t : thread_options((long)w * k.n * CH)) {
+          const FftChoice c{w, t, pl};
+          if (zop_choice_ok(k.n, CH, c)) add(c);
+        }
+  }
+  return out;
 }
 
 template <int P>

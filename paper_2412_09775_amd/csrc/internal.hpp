@@ -4,6 +4,9 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <functional>
+#include <vector>
+
 #include "common.hpp"
 
 namespace wo {
@@ -38,6 +41,44 @@ struct ScopedTiming {
     if (token) timing_end(token, s);
   }
 };
+
+// ---------------------------------------------------------------- FFT plan table
+//
+// Launch schedule of one FFT pass for one problem shape, chosen by timing
+// (wo_fft_tune) or by the default heuristics when the table has no entry.
+enum FftKind { kFftRowsR2C = 0, kFftRowsC2R = 1, kFftCols = 2, kFftZop = 3 };
+// plan: 0 = the compiled stages of the length when there are some, else the
+// runtime plan in the default radix order; 1 = runtime plan, default order
+// (8, 4, 2, 3, 5); 2 = runtime plan, reversed pass order; 3 = runtime plan,
+// odd radices first (5, 3, 8, 4, 2).
+struct FftKey {
+  int kind, n;
+  long m, batch;   // cols/zop: columns per plane (M); rows: 0.  batch: rows,
+                   // planes or patches of the launch
+  int extra;       // zop: P * 1000 + C * 10 + mode
+  bool operator<(const FftKey& o) const {
+    if (kind != o.kind) return kind < o.kind;
+    if (n != o.n) return n < o.n;
+    if (m != o.m) return m < o.m;
+    if (batch != o.batch) return batch < o.batch;
+    return extra < o.extra;
+  }
+};
+struct FftChoice {
+  int w;        // rows: lines per workgroup; cols/zop: tile width (columns)
+  int threads;  // workgroup size
+  int plan;
+};
+// Table entry for k, if any.
+bool fft_lookup(const FftKey& k, FftChoice* c);
+void fft_store(const FftKey& k, const FftChoice& c);
+// Every schedule the launcher of k accepts (the first is the default).
+std::vector<FftChoice> fft_candidates(const FftKey& k);
+// While a tuning run records, each tunable launch registers its key and a
+// closure that repeats it.
+bool fft_recording();
+void fft_record(const FftKey& k, std::function<hipError_t()> relaunch);
+bool make_plan_variant(int n, int variant, FftPlan* p);
 
 // Grouped row addressing: row i of group g lives at row g * stride + i.
 struct RowGroups {

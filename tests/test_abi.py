@@ -85,3 +85,31 @@ def test_null_and_small_workspace_are_rejected(lib):
     assert lib.wo_forward(mixed, 2, ctypes.c_void_p(1), ctypes.c_void_p(1), None,
                           ctypes.c_void_p(1), ctypes.c_void_p(1), 1 << 40, None) == -1
     assert lib.wo_strerror(-5).decode().startswith("transfer-function support")
+
+
+def test_fft_schedule_table_host_logic(lib):
+    """Candidate enumeration, import validation and export round trip (host only)."""
+    api.fft_plans_clear()
+    for key, n in (("cols 96 41 48 0", 96), ("rows_r2c 80 0 2304 0", 80), ("zop 24 3936 1 2011", 24)):
+        cands = api.fft_candidates(key)
+        assert len(cands) >= 2 and len(set(cands)) == len(cands)
+        for ln in cands:
+            f = ln.split()
+            assert " ".join(f[:5]) == key
+            w, thr, plan = map(int, f[5:])
+            assert 64 <= thr <= 1024 and thr % 64 == 0 and 0 <= plan <= 3 and w >= 1
+    # 80 = 8*2*5 has three distinct radix orders; 96 = 8*4*3 also; 24 = 8*3 two
+    assert {int(ln.split()[-1]) for ln in api.fft_candidates("rows_r2c 80 0 2304 0")} == {0, 2, 3}
+    assert {int(ln.split()[-1]) for ln in api.fft_candidates("zop 24 3936 1 2011")} == {0, 2}
+    pick = api.fft_candidates("cols 96 41 48 0")[-1]
+    api.fft_plans_import(pick)
+    assert api.fft_plans_export() == pick + "\n"
+    for bad in ("cols 96 41 48 0 64 64 0",       # 64 x 96 elements need 768 threads or more
+                "cols 96 41 48 0 1 100 0",       # not a multiple of 64
+                "zop 24 3936 1 2011 1 64 7",     # no such plan
+                "nonsense 1 2 3"):
+        with pytest.raises(api.WoError):
+            api.fft_plans_import(bad)
+    assert api.fft_plans_export() == pick + "\n"   # a rejected import changes nothing
+    api.fft_plans_clear()
+    assert api.fft_plans_export() == ""
