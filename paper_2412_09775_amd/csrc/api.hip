@@ -310,8 +310,9 @@ TuneLayout tune_layout(const wo_optics* o, int32_t n, int32_t starts) {
   L.off_pp = take((size_t)L.nv * L.tiles * sizeof(double));
   L.off_lp = take((size_t)L.nv * L.lbpp * sizeof(double));
   L.off_dp = take((size_t)L.nv * L.dwpp * sizeof(double));
-  L.off_gp = take((size_t)L.nv * Z * L.tiles * 4 * sizeof(double));
-  L.off_ip = take((size_t)L.nv * L.tiles * 4 * sizeof(double));
+  const long gt = grad_tiles(sm);
+  L.off_gp = take((size_t)L.nv * Z * gt * 4 * sizeof(double));
+  L.off_ip = take((size_t)L.nv * gt * 4 * sizeof(double));
   L.off_ropt = take((size_t)n * sizeof(DevOptics));
   L.off_reta = take((size_t)n * sizeof(float));
   L.total = b;
@@ -479,7 +480,8 @@ int validate_thin(const wo_optics* o, int32_t n) {
   for (int i = 0; i < n; ++i) {
     int st = check_sampling(&o[i]);
     if (st) return st;
-    if (o[i].model != WO_MODEL_LABELFREE_THIN || o[i].nz < 2) return WO_EUNSUPPORTED;
+    if (o[i].model != WO_MODEL_LABELFREE_THIN || o[i].nz < 2 || o[i].ny > 2048)
+      return WO_EUNSUPPORTED;
     st = check_optics(&o[i]);
     if (st) return st;
   }

@@ -231,119 +231,170 @@ hipError_t launch_tf_rows_bwd(const double* partials, const Sampling& sm, int nv
 // ------------------------------------------------------------------ backward columns + contraction
 
 // Inverse Y transform of u_A, u_B columns, then per lateral frequency the
-// contraction 4 Re(U_B dB/dtheta + U_A dA/dtheta).  gpart[((v*Z + z)*tiles + tile)*4 + j];
-// plane-0 workgroups also write dI_bg/dtheta partials to ipart[(v*tiles + tile)*4 + j].
+// contraction 4 Re(U_B dB/dtheta + U_A dA/dtheta).  A workgroup owns one column
+// tile and a chunk of ZC planes; the pupils and their derivatives, which do not
+// depend on z, are evaluated once.  gpart[((v*nzc + chunk)*tiles + tile)*4 + j];
+// the first chunk also writes dI_bg/dtheta partials to ipart[(v*tiles + tile)*4 + j].
 template <int NS>
-__global__ __launch_bounds__(1024) void k_tf_grad_y(const DevOptics* __restrict__ opt, Sampling sm,
+__global__ __launch_bounds__(512) void k_tf_grad_y(const DevOptics* __restrict__ opt, Sampling sm,
                                                     const float2* __restrict__ ab,
                                                     double* __restrict__ gpart,
                                                     double* __restrict__ ipart, int W,
-                                                    long tiles_x, FftPlan plan) {
+                                                    long tiles_x, int ZC, FftPlan plan) {
   extern __shared__ float2 smem[];
   __shared__ double red[kMaxThreads / 64];
+  constexpr int EPT = kEmax / 2;   // elements of a thread: Y * W <= threads * kEmax / 2
   const int Y = sm.ny, X = sm.nx, Z = sm.nz;
   float2* tw = smem;
   float2* buf = smem + Y;
   const int tid = threadIdx.x, nthr = blockDim.x;
   fill_twiddles(tw, Y, tid, nthr);
-  const long tile = blockIdx.x % tiles_x;
-  const long vz = blockIdx.x / tiles_x;
-  const int z = (int)(vz % Z);
-  const long v = vz / Z;
+  const long bid = xcd_block();
+  const long tile = bid % tiles_x;
+  const long rest = bid / tiles_x;
+  const int nzc = (Z + ZC - 1) / ZC;
+  const int zc = (int)(rest % nzc);
+  const long v = rest / nzc;
   const DevOptics o = opt[v];
   const int x0 = (int)(tile * W);
-  gather_to_lds(buf, Y * 2 * W, tid, nthr, [&](int e) {
-    const int ky = e / (2 * W);
-    const int r = e - ky * 2 * W;
-    const int f = r / W, w = r - f * W;
-    const int kx = x0 + w;
-    return kx < X ? ab[(((v * 2 + f) * Z + z) * (long)Y + ky) * X + kx] : make_float2(0.f, 0.f);
-  });
-  __syncthreads();
-  fft_lines<NS, 0, true>(buf, LdsLines{2 * W, 2 * W, 1, true}, plan, tw, 1.f, tid, nthr);
-  const double hw = soft_halfwidth(o, sm);
-  const double km = o.n_medium / o.wavelength;
-  const double rd = o.na_det / o.wavelength, ri = o.na_ill / o.wavelength;
-  double cy, cx;
-  source_centre(o, &cy, &cx);
-  const double rq0 = o.n_medium * sin(o.tilt_zenith) / o.wavelength;
-  const double drq0 = o.n_medium * cos(o.tilt_zenith) / o.wavelength;
-  const double sa = sin(o.tilt_azimuth), ca = cos(o.tilt_azimuth);
-  const double dzr = plane_z(z, sm) - o.defocus;
-  double g[4] = {0.0, 0.0, 0.0, 0.0};
-  double di[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int e = tid; e < Y * W; e += nthr) {
-    const int ky = e / W, w = e - ky * W;
-    const int kx = x0 + w;
-    if (kx >= X) continue;
-    const double fy = fftfreq(ky, Y, sm.dy), fx = fftfreq(kx, X, sm.dx);
-    const double rp = sqrt(fy * fy + fx * fx);
-    const double P = disc(fy, fx, rd, hw);
-    const double dP = edge_slope(rd - rp, hw) / o.wavelength;     // dP / dNA_det
-    const double qy = fy - cy, qx = fx - cx;
-    const double rq = sqrt(qy * qy + qx * qx);
-    const double S = disc(qy, qx, ri, hw);
-    const double sl = edge_slope(ri - rq, hw);
-    const double uy = rq > 0.0 ? qy / rq : 0.0, ux = rq > 0.0 ? qx / rq : 0.0;
-    const double dSy = sl * uy, dSx = sl * ux;                     // dS / d(cy, cx)
-    const double dSz = dSy * drq0 * sa + dSx * drq0 * ca;          // dS / d zenith
-    const double dSa = dSy * rq0 * ca - dSx * rq0 * sa;            // dS / d azimuth
-    if (z == 0) {
+  // per element: phase rate 2 kz (FP64, the phase needs it) and the pupil
+  // products of the contraction (FP32)
+  double tkz[EPT];
+  float SP[EPT], gkP[EPT], SdP[EPT], gkdP[EPT], dSzP[EPT], dSaP[EPT];
+  {
+    const double hw = soft_halfwidth(o, sm);
+    const double km = o.n_medium / o.wavelength;
+    const double rd = o.na_det / o.wavelength, ri = o.na_ill / o.wavelength;
+    double cy, cx;
+    source_centre(o, &cy, &cx);
+    const double rq0 = o.n_medium * sin(o.tilt_zenith) / o.wavelength;
+    const double drq0 = o.n_medium * cos(o.tilt_zenith) / o.wavelength;
+    const double sa = sin(o.tilt_azimuth), ca = cos(o.tilt_azimuth);
+    double di[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+      tkz[i] = 0.0;
+      SP[i] = gkP[i] = SdP[i] = gkdP[i] = dSzP[i] = dSaP[i] = 0.f;
+      const int e = tid + i * nthr;
+      if (e >= Y * W) continue;
+      const int ky = e / W, w = e - ky * W;
+      const int kx = x0 + w;
+      if (kx >= X) continue;
+      const double fy = fftfreq(ky, Y, sm.dy), fx = fftfreq(kx, X, sm.dx);
+      const double rp = sqrt(fy * fy + fx * fx);
+      const double P = disc(fy, fx, rd, hw);
+      const double dP = edge_slope(rd - rp, hw) / o.wavelength;     // dP / dNA_det
+      const double qy = fy - cy, qx = fx - cx;
+      const double rq = sqrt(qy * qy + qx * qx);
+      const double S = disc(qy, qx, ri, hw);
+      const double sl = edge_slope(ri - rq, hw);
+      const double uy = rq > 0.0 ? qy / rq : 0.0, ux = rq > 0.0 ? qx / rq : 0.0;
+      const double dSy = sl * uy, dSx = sl * ux;                     // dS / d(cy, cx)
+      const double dSz = dSy * drq0 * sa + dSx * drq0 * ca;          // dS / d zenith
+      const double dSa = dSy * rq0 * ca - dSx * rq0 * sa;            // dS / d azimuth
       di[1] += 2.0 * S * P * dP;
       di[2] += dSz * P * P;
       di[3] += dSa * P * P;
+      if (P == 0.0 && dP == 0.0) continue;
+      const double kz = sqrt(fmax(km * km - rp * rp, 0.0));
+      const double gk = kz > 0.0 ? km / kz : 0.0;
+      tkz[i] = 2.0 * kz;
+      // A = S P e, B = P (i km / kz) e with e = e^{i 2 pi kz (z - dz0)}
+      SP[i] = (float)(S * P);
+      gkP[i] = (float)(gk * P);
+      SdP[i] = (float)(S * dP);
+      gkdP[i] = (float)(gk * dP);
+      dSzP[i] = (float)(dSz * P);
+      dSaP[i] = (float)(dSa * P);
     }
-    if (P == 0.0 && dP == 0.0) continue;
-    const double kz = sqrt(fmax(km * km - rp * rp, 0.0));
-    const double arg = 2.0 * kz * dzr;
-    const float red_arg = (float)(arg - 2.0 * rint(0.5 * arg));
-    float snf, csf;
-    sincospif(red_arg, &snf, &csf);
-    const double cs = csf, sn = snf;
-    const float2 UA = buf[ky * 2 * W + w];
-    const float2 UB = buf[ky * 2 * W + W + w];
-    // Re(U * q e^{i phi}) for a complex scalar q = (qr, qi)
-    const double ua_re = UA.x * cs - UA.y * sn, ua_im = UA.x * sn + UA.y * cs;   // U_A e^{i phi}
-    const double ub_re = UB.x * cs - UB.y * sn, ub_im = UB.x * sn + UB.y * cs;   // U_B e^{i phi}
-    // A = S P e, B = P (i km / kz) e; d/d defocus multiplies by -i 2 pi kz
-    const double gk = kz > 0.0 ? km / kz : 0.0;
-    const double tpk = 2.0 * M_PI * kz;
-    // Re(U_A A (-i tpk)) = tpk * S P * Im(U_A e)
-    // Re(U_B B (-i tpk)) = Re(U_B e * i gk P * (-i tpk)) = tpk gk P Re(U_B e)
-    g[0] += tpk * (S * P * ua_im + gk * P * ub_re);
-    // d/dNA: A' = S dP e, B' = dP i gk e -> Re(U_B e i gk dP) = -gk dP Im(U_B e)
-    g[1] += S * dP * ua_re - gk * dP * ub_im;
-    g[2] += dSz * P * ua_re;
-    g[3] += dSa * P * ua_re;
+    if (zc == 0) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const double t = block_sum_d(di[j], red);
+        if (tid == 0) ipart[(v * tiles_x + tile) * 4 + j] = t;
+      }
+    }
+  }
+  double g[4] = {0.0, 0.0, 0.0, 0.0};
+  const int zend = min(Z, (zc + 1) * ZC);
+  for (int z = zc * ZC; z < zend; ++z) {
+    gather_to_lds(buf, Y * 2 * W, tid, nthr, [&](int e) {
+      const int ky = e / (2 * W);
+      const int r = e - ky * 2 * W;
+      const int f = r / W, w = r - f * W;
+      const int kx = x0 + w;
+      return kx < X ? ab[(((v * 2 + f) * Z + z) * (long)Y + ky) * X + kx] : make_float2(0.f, 0.f);
+    });
+    __syncthreads();
+    fft_lines<NS, 0, true>(buf, LdsLines{2 * W, 2 * W, 1, true, pow2_shift(2 * W)}, plan, tw, 1.f, tid,
+                             nthr);
+    const double dzr = plane_z(z, sm) - o.defocus;
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+      const int e = tid + i * nthr;
+      if (e >= Y * W || (tkz[i] == 0.0 && SP[i] == 0.f && SdP[i] == 0.f && gkdP[i] == 0.f &&
+                         dSzP[i] == 0.f && dSaP[i] == 0.f))
+        continue;
+      const int ky = e / W, w = e - ky * W;
+      const double arg = tkz[i] * dzr;
+      const float red_arg = (float)(arg - 2.0 * rint(0.5 * arg));
+      float snf, csf;
+      sincospif(red_arg, &snf, &csf);
+      const double cs = csf, sn = snf;
+      const float2 UA = buf[ky * 2 * W + w];
+      const float2 UB = buf[ky * 2 * W + W + w];
+      const double ua_re = UA.x * cs - UA.y * sn, ua_im = UA.x * sn + UA.y * cs;   // U_A e^{i phi}
+      const double ub_re = UB.x * cs - UB.y * sn, ub_im = UB.x * sn + UB.y * cs;   // U_B e^{i phi}
+      // d/d defocus multiplies A and B by -i 2 pi kz:
+      //   Re(U_A A (-i tpk)) = tpk S P Im(U_A e); Re(U_B B (-i tpk)) = tpk gk P Re(U_B e)
+      g[0] += M_PI * tkz[i] * ((double)SP[i] * ua_im + (double)gkP[i] * ub_re);
+      // d/dNA: A' = S dP e, B' = dP i gk e -> Re(U_B e i gk dP) = -gk dP Im(U_B e)
+      g[1] += (double)SdP[i] * ua_re - (double)gkdP[i] * ub_im;
+      g[2] += (double)dSzP[i] * ua_re;
+      g[3] += (double)dSaP[i] * ua_re;
+    }
+    __syncthreads();
   }
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     const double t = block_sum_d(4.0 * g[j], red);
-    if (tid == 0) gpart[(vz * tiles_x + tile) * 4 + j] = t;
-  }
-  if (z == 0) {
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const double t = block_sum_d(di[j], red);
-      if (tid == 0) ipart[(v * tiles_x + tile) * 4 + j] = t;
-    }
+    if (tid == 0) gpart[((v * nzc + zc) * tiles_x + tile) * 4 + j] = t;
   }
 }
+
+// Column tile of the gradient kernel: at most 512 threads (2 Y W <= 512 kEmax),
+// which leaves each thread the registers for its z-independent factors.
+static int grad_tile_width(const Sampling& sm) {
+  int W = 16;
+  while (W > 1 && 2L * W * sm.ny > 512L * kEmax) W /= 2;
+  return W;
+}
+
+long grad_tiles(const Sampling& sm) {
+  const int W = grad_tile_width(sm);
+  return (sm.nx + W - 1) / W;
+}
+
+// z chunk of the gradient kernel (the reduction reads ceil(nz / chunk) * tiles
+// partials per patch).
+int grad_z_chunk(const Sampling& sm, int nv) { return tf_z_chunk(sm, grad_tiles(sm), nv); }
 
 hipError_t launch_tf_grad_y(const DevOptics* opt, const Sampling& sm, int nv, const float2* ab,
                             double* gpart, double* ipart, hipStream_t s) {
   FftPlan plan;
   if (!make_plan(sm.ny, &plan)) return hipErrorInvalidValue;
-  const int W = tf_tile_width(sm);
-  const long tiles = (sm.nx + W - 1) / W;
-  const long nwg = tiles * sm.nz * (long)nv;
+  if (2L * sm.ny > 512L * kEmax) return hipErrorInvalidValue;
+  const int W = grad_tile_width(sm);
+  const long tiles = grad_tiles(sm);
+  const int ZC = grad_z_chunk(sm, nv);
+  const long nwg = tiles * ((sm.nz + ZC - 1) / ZC) * (long)nv;
   const int thr = threads_for((long)sm.ny * 2 * W);
   const size_t lds = (size_t)(sm.ny + sm.ny * 2 * W) * sizeof(float2);
   ScopedTiming _t("k_tf_grad_y", s);
 #define X_(NN)                                                                                   \
   case NN:                                                                                       \
     hipLaunchKernelGGL((k_tf_grad_y<NN>), dim3((unsigned)nwg), dim3(thr), lds, s, opt, sm, ab, gpart, \
-                       ipart, W, tiles, plan);                                                   \
+                       ipart, W, tiles, ZC, plan);                                               \
     return hipGetLastError();
   switch (sm.ny) {
     WO_LATERAL_SIZES(X_)
@@ -352,7 +403,7 @@ hipError_t launch_tf_grad_y(const DevOptics* opt, const Sampling& sm, int nv, co
   }
 #undef X_
   hipLaunchKernelGGL((k_tf_grad_y<0>), dim3((unsigned)nwg), dim3(thr), lds, s, opt, sm, ab, gpart, ipart,
-                     W, tiles, plan);
+                     W, tiles, ZC, plan);
   return hipGetLastError();
 }
 
@@ -363,9 +414,10 @@ hipError_t launch_tf_grad_y(const DevOptics* opt, const Sampling& sm, int nv, co
 __global__ __launch_bounds__(256) void k_adam(DevOptics* __restrict__ opt,
                                               TuneState* __restrict__ st, Sampling sm,
                                               const double* __restrict__ ppart, long tiles_x,
+                                              long gtiles,
                                               const double* __restrict__ lpart, long lbpp,
                                               const double* __restrict__ dpart, long dwpp,
-                                              const double* __restrict__ gpart,
+                                              const double* __restrict__ gpart, long gn,
                                               const double* __restrict__ ipart, int update) {
   __shared__ double red[4];
   const long v = blockIdx.x;
@@ -381,13 +433,12 @@ __global__ __launch_bounds__(256) void k_adam(DevOptics* __restrict__ opt,
   for (long i = tid; i < tiles_x; i += blockDim.x) acc += ppart[v * tiles_x + i];
   const double ibg = block_sum_d(acc, red);
   double gj[4], dij[4];
-  const long gn = (long)sm.nz * tiles_x;
   for (int j = 0; j < 4; ++j) {
     acc = 0.0;
     for (long i = tid; i < gn; i += blockDim.x) acc += gpart[(v * gn + i) * 4 + j];
     gj[j] = block_sum_d(acc, red);
     acc = 0.0;
-    for (long i = tid; i < tiles_x; i += blockDim.x) acc += ipart[(v * tiles_x + i) * 4 + j];
+    for (long i = tid; i < gtiles; i += blockDim.x) acc += ipart[(v * gtiles + i) * 4 + j];
     dij[j] = block_sum_d(acc, red);
   }
   if (tid != 0) return;
@@ -426,8 +477,11 @@ hipError_t launch_adam(DevOptics* opt, TuneState* st, const Sampling& sm, int nv
                        const double* gpart, const double* ipart, int update, hipStream_t s) {
   const long tiles_x = (sm.nx + tf_tile_width(sm) - 1) / tf_tile_width(sm);
   { ScopedTiming _t("k_adam", s);
-  hipLaunchKernelGGL(k_adam, dim3(nv), dim3(256), 0, s, opt, st, sm, ppart, tiles_x, lpart,
-                     loss_blocks(sm), dpart, bwd_wg_per_patch(sm), gpart, ipart, update); }
+  const int ZC = grad_z_chunk(sm, nv);
+  const long gt = grad_tiles(sm);
+  const long gn = (long)((sm.nz + ZC - 1) / ZC) * gt;
+  hipLaunchKernelGGL(k_adam, dim3(nv), dim3(256), 0, s, opt, st, sm, ppart, tiles_x, gt, lpart,
+                     loss_blocks(sm), dpart, bwd_wg_per_patch(sm), gpart, gn, ipart, update); }
   return hipGetLastError();
 }
 

@@ -227,7 +227,16 @@ struct LdsLines {
   int es;     // element stride
   int ls;     // line stride
   bool linefast;
+  int shift = -1;   // log2(nl) when nl is a power of two (slot -> line by masks), else -1
 };
+
+// log2(n) for a power of two n, else -1.
+__host__ __device__ inline int pow2_shift(int n) {
+  if (n <= 0 || (n & (n - 1))) return -1;
+  int s = 0;
+  while ((1 << s) < n) ++s;
+  return s;
+}
 
 template <int R>
 __device__ __forceinline__ void stockham_pass(float2* lds, const LdsLines L, int n, int ns,
@@ -244,8 +253,10 @@ __device__ __forceinline__ void stockham_pass(float2* lds, const LdsLines L, int
     base[b] = -1;
     if (j < total) {
       int l, k;
-      if (L.linefast) { l = j % L.nl; k = j / L.nl; }
-      else { k = j % nb; l = j / nb; }
+      if (L.linefast) {
+        if (L.shift >= 0) { l = j & (L.nl - 1); k = j >> L.shift; }
+        else { l = j % L.nl; k = j / L.nl; }
+      } else { k = j % nb; l = j / nb; }
       const int lb = l * L.ls;
       const int km = k % ns;
       base[b] = lb;
@@ -293,6 +304,18 @@ __device__ __forceinline__ void lds_fft(float2* lds, const LdsLines L, const Fft
     }
     ns *= R;
   }
+}
+
+// Workgroup index remapped so that each XCD (accelerator die, own L2) runs a
+// contiguous range of logical indices: the hardware hands workgroups to the 8
+// XCDs in turn, so physical index b runs on XCD b % 8.  Neighbouring column
+// tiles then share an L2 and the halves of cache lines they split.
+constexpr unsigned kXcds = 8;
+__device__ __forceinline__ long xcd_block() {
+  const unsigned n = gridDim.x, b = blockIdx.x;
+  const unsigned q = n / kXcds, r = n % kXcds;
+  const unsigned x = b % kXcds, k = b / kXcds;
+  return (long)(x < r ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k);
 }
 
 // ---------------------------------------------------------------- optics
@@ -412,8 +435,8 @@ struct StaticPlan {
 };
 
 template <int N, int R, int NS, int NL, bool LF>
-__device__ __forceinline__ void static_pass(float2* lds, int nl_rt, int es, int ls, const float2* tw,
-                                            float s, int tid, int nthr) {
+__device__ __forceinline__ void static_pass(float2* lds, int nl_rt, int es, int ls, int shift,
+                                            const float2* tw, float s, int tid, int nthr) {
   constexpr int NB = N / R;
   constexpr int BPT = (kEmax + R - 1) / R;
   constexpr int TWS = N / (NS * R);
@@ -427,8 +450,10 @@ __device__ __forceinline__ void static_pass(float2* lds, int nl_rt, int es, int 
     base[b] = -1;
     if (j < total) {
       int l, k;
-      if (LF) { l = j % nl; k = j / nl; }
-      else { k = j % NB; l = j / NB; }
+      if (LF) {
+        if (NL == 0 && shift >= 0) { l = j & (nl - 1); k = j >> shift; }
+        else { l = j % nl; k = j / nl; }
+      } else { k = j % NB; l = j / NB; }
       const int lb = l * ls;
       const int km = k % NS;
       base[b] = lb;
@@ -460,12 +485,12 @@ __device__ __forceinline__ void static_pass(float2* lds, int nl_rt, int es, int 
 }
 
 template <int N, int NL, bool LF, int Q = 0>
-__device__ __forceinline__ void static_fft(float2* lds, int nl_rt, int es, int ls, const float2* tw,
-                                           float s, int tid, int nthr) {
+__device__ __forceinline__ void static_fft(float2* lds, int nl_rt, int es, int ls, int shift,
+                                           const float2* tw, float s, int tid, int nthr) {
   if constexpr (Q < StaticPlan<N>::passes()) {
-    static_pass<N, StaticPlan<N>::radix(Q), StaticPlan<N>::span(Q), NL, LF>(lds, nl_rt, es, ls, tw, s,
-                                                                            tid, nthr);
-    static_fft<N, NL, LF, Q + 1>(lds, nl_rt, es, ls, tw, s, tid, nthr);
+    static_pass<N, StaticPlan<N>::radix(Q), StaticPlan<N>::span(Q), NL, LF>(lds, nl_rt, es, ls, shift,
+                                                                            tw, s, tid, nthr);
+    static_fft<N, NL, LF, Q + 1>(lds, nl_rt, es, ls, shift, tw, s, tid, nthr);
   }
 }
 
@@ -474,7 +499,7 @@ __device__ __forceinline__ void static_fft(float2* lds, int nl_rt, int es, int l
 template <int NSTAT, int NL, bool LF>
 __device__ __forceinline__ void fft_lines(float2* lds, const LdsLines& L, const FftPlan& p,
                                           const float2* tw, float s, int tid, int nthr) {
-  if constexpr (NSTAT > 0) static_fft<NSTAT, NL, LF>(lds, L.nl, L.es, L.ls, tw, s, tid, nthr);
+  if constexpr (NSTAT > 0) static_fft<NSTAT, NL, LF>(lds, L.nl, L.es, L.ls, L.shift, tw, s, tid, nthr);
   else lds_fft(lds, L, p, tw, s, tid, nthr);
 }
 

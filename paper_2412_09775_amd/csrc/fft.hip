@@ -35,22 +35,23 @@ __global__ __launch_bounds__(1024) void k_rows_r2c(const float* __restrict__ in,
     rout[t] = r < nrows ? group_row(r, g.rows_per_group, g.out_stride) : -1;
   }
   __syncthreads();
-  gather_to_lds(buf, nl * X, tid, nthr, [&](int e) {
-    const int l = e / X, i = e - l * X;
+  const int Xc = NS > 0 ? NS : X;   // compile-time length for the index arithmetic
+  gather_to_lds(buf, nl * Xc, tid, nthr, [&](int e) {
+    const int l = e / Xc, i = e - l * Xc;
     const float a = in[rin[2 * l] * X + i];
     const float b = rin[2 * l + 1] >= 0 ? in[rin[2 * l + 1] * X + i] : 0.f;
     return make_float2(a, b);
   }, [&] { fill_twiddles(tw, X, tid, nthr); });
   __syncthreads();
   fft_lines<NS, 0, false>(buf, LdsLines{nl, 1, X, false}, plan, tw, -1.f, tid, nthr);
-  const int Xh = X / 2 + 1;
+  const int Xh = Xc / 2 + 1;
 #pragma unroll
   for (int i = 0; i < kEmax; ++i) {
     const int e = tid + i * nthr;
     if (e < nl * Xh) {
       const int l = e / Xh, k = e - l * Xh;
-      const float2 zk = buf[l * X + k];
-      const float2 zm = buf[l * X + (k == 0 ? 0 : X - k)];
+      const float2 zk = buf[l * Xc + k];
+      const float2 zm = buf[l * Xc + (k == 0 ? 0 : Xc - k)];
       const float2 A = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y));
       const float2 B = make_float2(0.5f * (zk.y + zm.y), -0.5f * (zk.x - zm.x));
       out[rout[2 * l] * Xh + k] = A;
@@ -78,21 +79,22 @@ __global__ __launch_bounds__(1024) void k_rows_c2r(const float2* __restrict__ in
     rout[t] = r < nrows ? group_row(r, g.rows_per_group, g.out_stride) : -1;
   }
   __syncthreads();
-  const int Xh = X / 2 + 1;
-  gather_to_lds(buf, nl * X, tid, nthr, [&](int e) {
-    const int l = e / X, k = e - l * X;
-    const bool mirror = 2 * k > X;
-    const int kk = mirror ? X - k : k;
+  const int Xc = NS > 0 ? NS : X;   // compile-time length for the index arithmetic
+  const int Xh = Xc / 2 + 1;
+  gather_to_lds(buf, nl * Xc, tid, nthr, [&](int e) {
+    const int l = e / Xc, k = e - l * Xc;
+    const bool mirror = 2 * k > Xc;
+    const int kk = mirror ? Xc - k : k;
     float2 A = in[rin[2 * l] * Xh + kk];
     float2 B = rin[2 * l + 1] >= 0 ? in[rin[2 * l + 1] * Xh + kk] : make_float2(0.f, 0.f);
-    if (kk == 0 || 2 * kk == X) { A.y = 0.f; B.y = 0.f; }   // Re of the inverse ignores them
+    if (kk == 0 || 2 * kk == Xc) { A.y = 0.f; B.y = 0.f; }   // Re of the inverse ignores them
     if (mirror) { A.y = -A.y; B.y = -B.y; }
     return make_float2(A.x - B.y, A.y + B.x);
   }, [&] { fill_twiddles(tw, X, tid, nthr); });
   __syncthreads();
   fft_lines<NS, 0, false>(buf, LdsLines{nl, 1, X, false}, plan, tw, 1.f, tid, nthr);
-  scatter_from_lds(buf, nl * X, tid, nthr, [&](int e, float2 v) {
-    const int l = e / X, i = e - l * X;
+  scatter_from_lds(buf, nl * Xc, tid, nthr, [&](int e, float2 v) {
+    const int l = e / Xc, i = e - l * Xc;
     out[rout[2 * l] * X + i] = v.x * scale;
     if (rout[2 * l + 1] >= 0) out[rout[2 * l + 1] * X + i] = v.y * scale;
   });
@@ -205,26 +207,28 @@ template <int NS, int WS>
 __global__ __launch_bounds__(1024) void k_cols(float2* __restrict__ data, int N, long M, int Wrt,
                                                long tiles_m, long planes_per_group,
                                                long group_stride, FftPlan plan, float sign) {
-  const int W = WS > 0 ? WS : Wrt;
+  const int W = WS > 0 ? WS : Wrt;             // a power of two
+  const int wsh = WS > 0 ? pow2_shift(WS) : pow2_shift(Wrt);
   extern __shared__ float2 smem[];
   float2* tw = smem;
   float2* buf = smem + N;
   const int tid = threadIdx.x, nthr = blockDim.x;
-  const long bid = blockIdx.x;
+  const long bid = xcd_block();
   const long tile = bid % tiles_m;
   const long plane = bid / tiles_m;
   const long pg = plane / planes_per_group, pi = plane - pg * planes_per_group;
   float2* base = data + (pg * group_stride + pi) * (long)N * M;
   const long m0 = tile * W;
   const int weff = (int)min((long)W, M - m0);
-  gather_to_lds(buf, N * W, tid, nthr, [&](int e) {
-    const int n = e / W, w = e - n * W;
+  const int Nc = NS > 0 ? NS : N;
+  gather_to_lds(buf, Nc * W, tid, nthr, [&](int e) {
+    const int n = e >> wsh, w = e & (W - 1);
     return w < weff ? base[(long)n * M + m0 + w] : make_float2(0.f, 0.f);
-  }, [&] { fill_twiddles(tw, N, tid, nthr); });
+  }, [&] { fill_twiddles(tw, Nc, tid, nthr); });
   __syncthreads();
-  fft_lines<NS, WS, true>(buf, LdsLines{W, W, 1, true}, plan, tw, sign, tid, nthr);
-  scatter_from_lds(buf, N * W, tid, nthr, [&](int e, float2 v) {
-    const int n = e / W, w = e - n * W;
+  fft_lines<NS, WS, true>(buf, LdsLines{W, W, 1, true, wsh}, plan, tw, sign, tid, nthr);
+  scatter_from_lds(buf, Nc * W, tid, nthr, [&](int e, float2 v) {
+    const int n = e >> wsh, w = e & (W - 1);
     if (w < weff) base[(long)n * M + m0 + w] = v;
   });
 }
@@ -249,7 +253,7 @@ constexpr int static_tile_width(int n) {
 
 static bool cols_choice_ok(int N, const FftChoice& c) {
   const long elems = (long)c.w * N;
-  return c.w >= 1 && c.w <= 64 && elems <= kMaxElems && threads_ok(c.threads, elems) &&
+  return pow2_shift(c.w) >= 0 && c.w <= 64 && elems <= kMaxElems && threads_ok(c.threads, elems) &&
          (long)(N + elems) * (long)sizeof(float2) <= lds_limit_bytes() && c.plan >= 0 && c.plan <= 3;
 }
 
@@ -418,9 +422,11 @@ __global__ __launch_bounds__(1024) void k_zop(float2* __restrict__ spec,
   float2* tw = smem;
   float2* buf = smem + Z;
   const int tid = threadIdx.x, nthr = blockDim.x;
-  const long bid = blockIdx.x;
+  const long bid = xcd_block();
   const long tile = bid % tiles_m;
   const long patch = bid / tiles_m;
+  const int Zc = NS > 0 ? NS : Z;   // compile-time length for the index arithmetic
+  const int wsh = pow2_shift(W);    // W is a power of two
   const int cin = mode == kModeForward ? P : C;
   const int cout = mode == kModeForward ? C : P;
   const int CH = cin > cout ? cin : cout;
@@ -432,7 +438,7 @@ __global__ __launch_bounds__(1024) void k_zop(float2* __restrict__ spec,
   const long ts = (long)Z * M;               // stride between (c, p) entries of the bank
   // Issue this thread's transfer-function loads first: they complete while the
   // data tile is loaded and transformed.  Frequency f = tid + i * nthr.
-  const int nfreq = Z * W;
+  const int nfreq = Zc * W;
   const int fpt = (nfreq + nthr - 1) / nthr;
   const bool prefetch = CT == 1 && P * fpt <= kTfPrefetch;
   float2 hreg[kTfPrefetch];
@@ -442,7 +448,7 @@ __global__ __launch_bounds__(1024) void k_zop(float2* __restrict__ spec,
       const int i = j / P, cp = j - i * P;
       const int f = tid + i * nthr;
       if (i < fpt && f < nfreq) {
-        const int z = f / W, w = f - z * W;
+        const int z = f >> wsh, w = f & (W - 1);
         hreg[j] = w < weff ? tp[cp * ts + (long)z * M + m0 + w] : make_float2(0.f, 0.f);
       }
     }
@@ -453,9 +459,9 @@ __global__ __launch_bounds__(1024) void k_zop(float2* __restrict__ spec,
 #pragma unroll
     for (int i = 0; i < kEmax; ++i) {
       const int e = tid + i * nthr;
-      if (e < cin * Z * W) {
-        const int w = e % W, r = e / W;
-        const int z = r % Z, ch = r / Z;
+      if (e < cin * Zc * W) {
+        const int w = e & (W - 1), r = e >> wsh;
+        const int z = r % Zc, ch = r / Zc;
         t[i] = w < weff ? sp[((long)ch * Z + z) * M + m0 + w] : make_float2(0.f, 0.f);
       }
     }
@@ -463,21 +469,22 @@ __global__ __launch_bounds__(1024) void k_zop(float2* __restrict__ spec,
 #pragma unroll
     for (int i = 0; i < kEmax; ++i) {
       const int e = tid + i * nthr;
-      if (e < cin * Z * W) {
-        const int w = e % W, r = e / W;
-        const int z = r % Z, ch = r / Z;
+      if (e < cin * Zc * W) {
+        const int w = e & (W - 1), r = e >> wsh;
+        const int z = r % Zc, ch = r / Zc;
         buf[(z * CH + ch) * W + w] = t[i];
       }
     }
   }
   __syncthreads();
-  fft_lines<NS, 0, true>(buf, LdsLines{cin * W, CH * W, 1, true}, plan, tw, -1.f, tid, nthr);
+  fft_lines<NS, 0, true>(buf, LdsLines{cin * W, CH * W, 1, true, pow2_shift(cin * W)}, plan, tw, -1.f,
+                         tid, nthr);
   if (prefetch) {
 #pragma unroll
     for (int i = 0; i < kTfPrefetch; ++i) {
       const int f = tid + i * nthr;
       if (i < fpt && f < nfreq) {
-        const int z = f / W, w = f - z * W;
+        const int z = f >> wsh, w = f & (W - 1);
         if (w < weff) {
           const long m = m0 + w;
           freq_op<P, 1>(buf + (long)z * CH * W + w, W,
@@ -488,7 +495,7 @@ __global__ __launch_bounds__(1024) void k_zop(float2* __restrict__ spec,
     }
   } else {
     for (int f = tid; f < nfreq; f += nthr) {
-      const int z = f / W, w = f - z * W;
+      const int z = f >> wsh, w = f & (W - 1);
       if (w >= weff) continue;
       const long m = m0 + w;
       const float2* hp = tp + (long)z * M + m;
@@ -498,24 +505,25 @@ __global__ __launch_bounds__(1024) void k_zop(float2* __restrict__ spec,
     }
   }
   __syncthreads();
-  fft_lines<NS, 0, true>(buf, LdsLines{cout * W, CH * W, 1, true}, plan, tw, 1.f, tid, nthr);
+  fft_lines<NS, 0, true>(buf, LdsLines{cout * W, CH * W, 1, true, pow2_shift(cout * W)}, plan, tw, 1.f,
+                         tid, nthr);
   {
     float2 t[kEmax];
 #pragma unroll
     for (int i = 0; i < kEmax; ++i) {
       const int e = tid + i * nthr;
-      if (e < cout * Z * W) {
-        const int w = e % W, r = e / W;
-        const int z = r % Z, ch = r / Z;
+      if (e < cout * Zc * W) {
+        const int w = e & (W - 1), r = e >> wsh;
+        const int z = r % Zc, ch = r / Zc;
         t[i] = buf[(z * CH + ch) * W + w];
       }
     }
 #pragma unroll
     for (int i = 0; i < kEmax; ++i) {
       const int e = tid + i * nthr;
-      if (e < cout * Z * W) {
-        const int w = e % W, r = e / W;
-        const int z = r % Z, ch = r / Z;
+      if (e < cout * Zc * W) {
+        const int w = e & (W - 1), r = e >> wsh;
+        const int z = r % Zc, ch = r / Zc;
         if (w < weff) sp[((long)ch * Z + z) * M + m0 + w] = t[i];
       }
     }
@@ -543,7 +551,7 @@ static void zop_launch(bool use_static, long nwg, int thr, size_t lds, hipStream
 
 static bool zop_choice_ok(int Z, int CH, const FftChoice& c) {
   const long elems = (long)c.w * Z * CH;
-  return c.w >= 1 && c.w <= 64 && elems <= kMaxElems && threads_ok(c.threads, elems) &&
+  return pow2_shift(c.w) >= 0 && c.w <= 64 && elems <= kMaxElems && threads_ok(c.threads, elems) &&
          (long)(Z + elems) * (long)sizeof(float2) <= lds_limit_bytes() && c.plan >= 0 && c.plan <= 3;
 }
 

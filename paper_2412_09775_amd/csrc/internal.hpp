@@ -116,6 +116,8 @@ hipError_t launch_set_params(DevOptics* dst, const DevOptics* host, int n, hipSt
 // Column tile width of the field kernel; the pupil-sum partials hold
 // ceil(nx / width) doubles per patch.
 int tf_tile_width(const Sampling& sm);
+// Planes per workgroup of the z-chunked field and gradient kernels.
+int tf_z_chunk(const Sampling& sm, long tiles_x, long npatch);
 hipError_t launch_tf_fields_y(const DevOptics* opt, const Sampling& sm, int npatch, float2* ab,
                               double* partials, hipStream_t s);
 hipError_t launch_tf_rows_labelfree(const double* partials, const Sampling& sm, int npatch,
@@ -130,6 +132,9 @@ hipError_t launch_tf_pol5_z(const DevOptics* opt, const Sampling& sm, int npatch
 hipError_t launch_set_tune(TuneState* dst, const TuneState* host, int n, hipStream_t s);
 long loss_blocks(const Sampling& sm);
 long bwd_wg_per_patch(const Sampling& sm);
+// Column tiles of the gradient kernel; its partials hold nz * tiles * 4 (at
+// most) and tiles * 4 doubles per virtual patch.
+long grad_tiles(const Sampling& sm);
 hipError_t launch_loss_grad(const DevOptics* opt, const TuneState* st, const Sampling& sm, int nv,
                             const float2* D, float2* bank, double* lpart, int data_div,
                             hipStream_t s);

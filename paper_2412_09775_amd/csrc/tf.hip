@@ -80,14 +80,17 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
 // ------------------------------------------------------------------ fields, inverse Y
 
 // ab layout: [patch][field][z][y][x] complex (field 0 = A or the fluorescence
-// field, field 1 = B).  Workgroups of plane 0 also write the tile's share of
-// the pupil sum (sum S P^2 for label-free, sum P^2 for fluorescence) to
+// field, field 1 = B).  A workgroup owns one column tile of one patch and a
+// chunk of ZC consecutive planes: the pupil values, which do not depend on z,
+// are evaluated once into registers; each plane then only needs its phase.
+// The workgroup of the first chunk also writes the tile's share of the pupil
+// sum (sum S P^2 for label-free, sum P^2 for fluorescence) to
 // partials[patch * tiles_x + tile].
-template <int NS>
+template <int NS, int NF>
 __global__ __launch_bounds__(1024) void k_tf_fields_y(const DevOptics* __restrict__ opt,
                                                       Sampling sm, float2* __restrict__ ab,
                                                       double* __restrict__ partials, int W,
-                                                      long tiles_x, FftPlan plan) {
+                                                      long tiles_x, int ZC, FftPlan plan) {
   __shared__ double red[kMaxThreads / 64];
   extern __shared__ float2 smem[];
   const int Y = sm.ny, X = sm.nx, Z = sm.nz;
@@ -95,68 +98,106 @@ __global__ __launch_bounds__(1024) void k_tf_fields_y(const DevOptics* __restric
   float2* buf = smem + Y;
   const int tid = threadIdx.x, nthr = blockDim.x;
   fill_twiddles(tw, Y, tid, nthr);
-  const long bid = blockIdx.x;
+  const long bid = xcd_block();
   const long tile = bid % tiles_x;
-  const long pz = bid / tiles_x;
-  const int z = (int)(pz % Z);
-  const long patch = pz / Z;
+  const long rest = bid / tiles_x;
+  const int nzc = (Z + ZC - 1) / ZC;
+  const int zc = (int)(rest % nzc);
+  const long patch = rest / nzc;
   const DevOptics o = opt[patch];
-  const bool fluor = sm.model == kFluor3D;
-  const int nf = fluor ? 1 : 2;
-  const double hw = soft_halfwidth(o, sm);
-  const double km = o.n_medium / o.wavelength;
-  const double rd = o.na_det / o.wavelength, ri = o.na_ill / o.wavelength;
-  double cy, cx;
-  source_centre(o, &cy, &cx);
-  const double dzr = plane_z(z, sm) - o.defocus;
+  constexpr bool fluor = NF == 1;   // one field (fluorescence) or A and B (label-free)
+  constexpr int nf = NF;
+  constexpr int EPT = kEmax / NF;   // elements of a thread: Y * W * NF <= threads * kEmax
   const int x0 = (int)(tile * W);
-  double psum = 0.0;
-  for (int e = tid; e < Y * W; e += nthr) {
-    const int ky = e / W, w = e - ky * W;
-    const int kx = x0 + w;
-    float2 A = make_float2(0.f, 0.f), B = make_float2(0.f, 0.f);
-    if (kx < X) {
-      const double fy = fftfreq(ky, Y, sm.dy), fx = fftfreq(kx, X, sm.dx);
-      const double P = disc(fy, fx, rd, hw);
-      if (P != 0.0) {
-        const double kz = sqrt(fmax(km * km - (fy * fy + fx * fx), 0.0));
-        // phase 2 pi kz (z - dz0): reduce the argument (in units of pi) in FP64 to
-        // [-1, 1], then evaluate sin/cos in FP32
-        const double arg = 2.0 * kz * dzr;
-        const float red = (float)(arg - 2.0 * rint(0.5 * arg));
-        float snf, csf;
-        sincospif(red, &snf, &csf);
-        const double sn = snf, cs = csf;
-        if (fluor) {
-          A = make_float2((float)(P * cs), (float)(P * sn));
-          psum += P * P;
-        } else {
-          const double S = disc(fy - cy, fx - cx, ri, hw);
-          psum += S * P * P;
-          A = make_float2((float)(S * P * cs), (float)(S * P * sn));
-          if (kz > 0.0) {
-            const double g = P * km / kz;          // P * (i k_m / kz) * e^{i phi}
-            B = make_float2((float)(-g * sn), (float)(g * cs));
+  // z-independent factors of this thread's elements e = tid + i * nthr
+  double tkz[EPT], sp[EPT], gg[fluor ? 1 : EPT];
+  {
+    const double hw = soft_halfwidth(o, sm);
+    const double km = o.n_medium / o.wavelength;
+    const double rd = o.na_det / o.wavelength, ri = o.na_ill / o.wavelength;
+    double cy, cx;
+    source_centre(o, &cy, &cx);
+    double psum = 0.0;
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+      tkz[i] = 0.0;
+      sp[i] = 0.0;
+      if (!fluor) gg[i] = 0.0;
+      const int e = tid + i * nthr;
+      if (e < Y * W) {
+        const int ky = e / W, w = e - ky * W;
+        const int kx = x0 + w;
+        if (kx < X) {
+          const double fy = fftfreq(ky, Y, sm.dy), fx = fftfreq(kx, X, sm.dx);
+          const double P = disc(fy, fx, rd, hw);
+          if (P != 0.0) {
+            const double kz = sqrt(fmax(km * km - (fy * fy + fx * fx), 0.0));
+            tkz[i] = 2.0 * kz;
+            if (fluor) {
+              sp[i] = P;
+              psum += P * P;
+            } else {
+              const double S = disc(fy - cy, fx - cx, ri, hw);
+              psum += S * P * P;
+              sp[i] = S * P;
+              if (kz > 0.0) gg[i] = P * km / kz;   // P * (i k_m / kz)
+            }
           }
         }
       }
     }
-    buf[ky * nf * W + w] = A;
-    if (!fluor) buf[ky * nf * W + W + w] = B;
+    if (zc == 0) {
+      const double tot = block_sum(psum, red);
+      if (tid == 0) partials[patch * tiles_x + tile] = tot;
+    }
   }
-  if (z == 0) {
-    const double tot = block_sum(psum, red);
-    if (tid == 0) partials[patch * tiles_x + tile] = tot;
+  const int zend = min(Z, (zc + 1) * ZC);
+  for (int z = zc * ZC; z < zend; ++z) {
+    const double dzr = plane_z(z, sm) - o.defocus;
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+      const int e = tid + i * nthr;
+      if (e < Y * W) {
+        const int ky = e / W, w = e - ky * W;
+        float2 A = make_float2(0.f, 0.f), B = make_float2(0.f, 0.f);
+        if (sp[i] != 0.0 || (!fluor && gg[i] != 0.0)) {
+          // phase 2 pi kz (z - dz0): reduce the argument (in units of pi) in FP64
+          // to [-1, 1], then evaluate sin/cos in FP32
+          const double arg = tkz[i] * dzr;
+          const float rr = (float)(arg - 2.0 * rint(0.5 * arg));
+          float snf, csf;
+          sincospif(rr, &snf, &csf);
+          const double sn = snf, cs = csf;
+          A = make_float2((float)(sp[i] * cs), (float)(sp[i] * sn));
+          if (!fluor) B = make_float2((float)(-gg[i] * sn), (float)(gg[i] * cs));   // e^{i phi} (i g)
+        }
+        buf[ky * nf * W + w] = A;
+        if (!fluor) buf[ky * nf * W + W + w] = B;
+      }
+    }
+    __syncthreads();
+    fft_lines<NS, 0, true>(buf, LdsLines{nf * W, nf * W, 1, true, pow2_shift(nf * W)}, plan, tw, 1.f,
+                           tid, nthr);
+    scatter_from_lds(buf, Y * nf * W, tid, nthr, [&](int e, float2 v) {
+      const int ky = e / (nf * W);
+      const int r = e - ky * nf * W;
+      const int f = r / W, w = r - f * W;
+      const int kx = x0 + w;
+      if (kx < X) ab[(((patch * nf + f) * Z + z) * (long)Y + ky) * X + kx] = v;
+    });
+    __syncthreads();
   }
-  __syncthreads();
-  fft_lines<NS, 0, true>(buf, LdsLines{nf * W, nf * W, 1, true}, plan, tw, 1.f, tid, nthr);
-  scatter_from_lds(buf, Y * nf * W, tid, nthr, [&](int e, float2 v) {
-    const int ky = e / (nf * W);
-    const int r = e - ky * nf * W;
-    const int f = r / W, w = r - f * W;
-    const int kx = x0 + w;
-    if (kx < X) ab[(((patch * nf + f) * Z + z) * (long)Y + ky) * X + kx] = v;
-  });
+}
+
+// Planes per workgroup of the z-chunked kernels: enough workgroups to fill the
+// device (about 2048), at most 16 planes.
+int tf_z_chunk(const Sampling& sm, long tiles_x, long npatch) {
+  const long wg_per_plane = tiles_x * npatch;
+  long zc = (long)sm.nz * wg_per_plane / 2048;
+  if (zc < 1) zc = 1;
+  if (zc > 16) zc = 16;
+  if (zc > sm.nz) zc = sm.nz;
+  return (int)zc;
 }
 
 int tf_tile_width(const Sampling& sm) {
@@ -174,14 +215,19 @@ hipError_t launch_tf_fields_y(const DevOptics* opt, const Sampling& sm, int npat
   const int nf = sm.model == kFluor3D ? 1 : 2;
   const int W = tf_tile_width(sm);
   const long tiles = (sm.nx + W - 1) / W;
-  const long nwg = tiles * sm.nz * (long)npatch;
+  const int ZC = tf_z_chunk(sm, tiles, npatch);
+  const long nwg = tiles * ((sm.nz + ZC - 1) / ZC) * (long)npatch;
   const int thr = threads_for((long)sm.ny * nf * W);
   const size_t lds = (size_t)(sm.ny + sm.ny * nf * W) * sizeof(float2);
   ScopedTiming _t("k_tf_fields_y", s);
 #define X_(NN)                                                                                   \
   case NN:                                                                                       \
-    hipLaunchKernelGGL((k_tf_fields_y<NN>), dim3((unsigned)nwg), dim3(thr), lds, s, opt, sm, ab,  \
-                       partials, W, tiles, plan);                                                \
+    if (nf == 2)                                                                                 \
+      hipLaunchKernelGGL((k_tf_fields_y<NN, 2>), dim3((unsigned)nwg), dim3(thr), lds, s, opt, \
+                         sm, ab, partials, W, tiles, ZC, plan);                                  \
+    else                                                                                         \
+      hipLaunchKernelGGL((k_tf_fields_y<NN, 1>), dim3((unsigned)nwg), dim3(thr), lds, s, opt, sm, \
+                         ab, partials, W, tiles, ZC, plan);                                      \
     return hipGetLastError();
   switch (sm.ny) {
     WO_LATERAL_SIZES(X_)
@@ -189,8 +235,12 @@ hipError_t launch_tf_fields_y(const DevOptics* opt, const Sampling& sm, int npat
       break;
   }
 #undef X_
-  hipLaunchKernelGGL((k_tf_fields_y<0>), dim3((unsigned)nwg), dim3(thr), lds, s, opt, sm, ab, partials,
-                     W, tiles, plan);
+  if (nf == 2)
+    hipLaunchKernelGGL((k_tf_fields_y<0, 2>), dim3((unsigned)nwg), dim3(thr), lds, s, opt, sm, ab,
+                       partials, W, tiles, ZC, plan);
+  else
+    hipLaunchKernelGGL((k_tf_fields_y<0, 1>), dim3((unsigned)nwg), dim3(thr), lds, s, opt, sm, ab,
+                       partials, W, tiles, ZC, plan);
   return hipGetLastError();
 }
 
@@ -407,7 +457,8 @@ __global__ __launch_bounds__(1024) void k_tf_pol5_z(const DevOptics* __restrict_
     }
   }
   __syncthreads();
-  fft_lines<NS, 0, true>(buf, LdsLines{2 * W, 2 * W, 1, true}, plan, tw, -1.f, tid, nthr);
+  fft_lines<NS, 0, true>(buf, LdsLines{2 * W, 2 * W, 1, true, pow2_shift(2 * W)}, plan, tw, -1.f, tid,
+                         nthr);
   float kr[20], ki[20];
   const DevOptics& o = opt[patch];
 #pragma unroll
