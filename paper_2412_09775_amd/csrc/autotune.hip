@@ -136,7 +136,8 @@ __global__ __launch_bounds__(1024) void k_tf_rows_bwd(const double* __restrict__
   extern __shared__ float2 smem[];
   __shared__ double red[kMaxThreads / 64];
   __shared__ double ibg_s;
-  const int Y = sm.ny, X = sm.nx, Z = sm.nz;
+  const int Y = sm.ny, Z = sm.nz;
+  const int X = NS > 0 ? NS : sm.nx;   // compile-time length for the index arithmetic
   float2* tw = smem;
   float2* buf = smem + X;
   const int tid = threadIdx.x, nthr = blockDim.x;
@@ -146,6 +147,7 @@ __global__ __launch_bounds__(1024) void k_tf_rows_bwd(const double* __restrict__
   const long wg = blockIdx.x - v * wg_per_patch;
   const long row0 = wg * (long)rows_per_wg;
   const int nr = (int)min((long)rows_per_wg, rpp - row0);
+  const int z0 = (int)(row0 / Y), y0 = (int)(row0 - (long)z0 * Y);
   float2* a_src = ab + (v * 2 + 0) * rpp * X;
   float2* b_src = ab + (v * 2 + 1) * rpp * X;
   if (tid == 0) {
@@ -166,8 +168,8 @@ __global__ __launch_bounds__(1024) void k_tf_rows_bwd(const double* __restrict__
   double dsum = 0.0;
   for (int e = tid; e < nr * X; e += nthr) {
     const int r = e / X, i = e - r * X;
-    const long row = row0 + r;
-    const long z = row / Y, y = row - z * Y;
+    int y = y0 + r, z = z0;
+    while (y >= Y) { y -= Y; ++z; }
     const float gph = gam[(((v * Z + z) * 2 + 0) * (long)Y + y) * X + i];
     const float gab = gam[(((v * Z + z) * 2 + 1) * (long)Y + y) * X + i];
     const float2 G = make_float2(gph, gab);
@@ -236,14 +238,14 @@ hipError_t launch_tf_rows_bwd(const double* partials, const Sampling& sm, int nv
 // depend on z, are evaluated once.  gpart[((v*nzc + chunk)*tiles + tile)*4 + j];
 // the first chunk also writes dI_bg/dtheta partials to ipart[(v*tiles + tile)*4 + j].
 template <int NS>
-__global__ __launch_bounds__(512) void k_tf_grad_y(const DevOptics* __restrict__ opt, Sampling sm,
+__global__ __launch_bounds__(1024) void k_tf_grad_y(const DevOptics* __restrict__ opt, Sampling sm,
                                                     const float2* __restrict__ ab,
                                                     double* __restrict__ gpart,
                                                     double* __restrict__ ipart, int W,
                                                     long tiles_x, int ZC, FftPlan plan) {
   extern __shared__ float2 smem[];
   __shared__ double red[kMaxThreads / 64];
-  constexpr int EPT = kEmax / 2;   // elements of a thread: Y * W <= threads * kEmax / 2
+  constexpr int EPT = 2;   // lateral frequencies of a thread: Y * W <= 2 * threads
   const int Y = sm.ny, X = sm.nx, Z = sm.nz;
   float2* tw = smem;
   float2* buf = smem + Y;
@@ -257,6 +259,7 @@ __global__ __launch_bounds__(512) void k_tf_grad_y(const DevOptics* __restrict__
   const long v = rest / nzc;
   const DevOptics o = opt[v];
   const int x0 = (int)(tile * W);
+  const int wsh = pow2_shift(W);     // W is a power of two
   // per element: phase rate 2 kz (FP64, the phase needs it) and the pupil
   // products of the contraction (FP32)
   double tkz[EPT];
@@ -277,7 +280,7 @@ __global__ __launch_bounds__(512) void k_tf_grad_y(const DevOptics* __restrict__
       SP[i] = gkP[i] = SdP[i] = gkdP[i] = dSzP[i] = dSaP[i] = 0.f;
       const int e = tid + i * nthr;
       if (e >= Y * W) continue;
-      const int ky = e / W, w = e - ky * W;
+      const int ky = e >> wsh, w = e & (W - 1);
       const int kx = x0 + w;
       if (kx >= X) continue;
       const double fy = fftfreq(ky, Y, sm.dy), fx = fftfreq(kx, X, sm.dx);
@@ -318,16 +321,16 @@ __global__ __launch_bounds__(512) void k_tf_grad_y(const DevOptics* __restrict__
   double g[4] = {0.0, 0.0, 0.0, 0.0};
   const int zend = min(Z, (zc + 1) * ZC);
   for (int z = zc * ZC; z < zend; ++z) {
-    gather_to_lds(buf, Y * 2 * W, tid, nthr, [&](int e) {
-      const int ky = e / (2 * W);
-      const int r = e - ky * 2 * W;
-      const int f = r / W, w = r - f * W;
+    gather_to_lds<2 * EPT>(buf, Y * 2 * W, tid, nthr, [&](int e) {
+      const int ky = e >> (wsh + 1);
+      const int r = e & (2 * W - 1);
+      const int f = r >> wsh, w = r & (W - 1);
       const int kx = x0 + w;
       return kx < X ? ab[(((v * 2 + f) * Z + z) * (long)Y + ky) * X + kx] : make_float2(0.f, 0.f);
     });
     __syncthreads();
-    fft_lines<NS, 0, true>(buf, LdsLines{2 * W, 2 * W, 1, true, pow2_shift(2 * W)}, plan, tw, 1.f, tid,
-                             nthr);
+    fft_lines<NS, 0, true, 2 * EPT>(buf, LdsLines{2 * W, 2 * W, 1, true, pow2_shift(2 * W)}, plan, tw,
+                                    1.f, tid, nthr);
     const double dzr = plane_z(z, sm) - o.defocus;
 #pragma unroll
     for (int i = 0; i < EPT; ++i) {
@@ -335,23 +338,24 @@ __global__ __launch_bounds__(512) void k_tf_grad_y(const DevOptics* __restrict__
       if (e >= Y * W || (tkz[i] == 0.0 && SP[i] == 0.f && SdP[i] == 0.f && gkdP[i] == 0.f &&
                          dSzP[i] == 0.f && dSaP[i] == 0.f))
         continue;
-      const int ky = e / W, w = e - ky * W;
+      const int ky = e >> wsh, w = e & (W - 1);
       const double arg = tkz[i] * dzr;
       const float red_arg = (float)(arg - 2.0 * rint(0.5 * arg));
       float snf, csf;
       sincospif(red_arg, &snf, &csf);
-      const double cs = csf, sn = snf;
       const float2 UA = buf[ky * 2 * W + w];
       const float2 UB = buf[ky * 2 * W + W + w];
-      const double ua_re = UA.x * cs - UA.y * sn, ua_im = UA.x * sn + UA.y * cs;   // U_A e^{i phi}
-      const double ub_re = UB.x * cs - UB.y * sn, ub_im = UB.x * sn + UB.y * cs;   // U_B e^{i phi}
+      // per-term products in FP32 (their inputs are FP32), sums in FP64
+      const float ua_re = UA.x * csf - UA.y * snf, ua_im = UA.x * snf + UA.y * csf;   // U_A e^{i phi}
+      const float ub_re = UB.x * csf - UB.y * snf, ub_im = UB.x * snf + UB.y * csf;   // U_B e^{i phi}
+      const float tpk = (float)(M_PI * tkz[i]);                                       // 2 pi kz
       // d/d defocus multiplies A and B by -i 2 pi kz:
       //   Re(U_A A (-i tpk)) = tpk S P Im(U_A e); Re(U_B B (-i tpk)) = tpk gk P Re(U_B e)
-      g[0] += M_PI * tkz[i] * ((double)SP[i] * ua_im + (double)gkP[i] * ub_re);
+      g[0] += (double)(tpk * (SP[i] * ua_im + gkP[i] * ub_re));
       // d/dNA: A' = S dP e, B' = dP i gk e -> Re(U_B e i gk dP) = -gk dP Im(U_B e)
-      g[1] += (double)SdP[i] * ua_re - (double)gkdP[i] * ub_im;
-      g[2] += (double)dSzP[i] * ua_re;
-      g[3] += (double)dSaP[i] * ua_re;
+      g[1] += (double)(SdP[i] * ua_re - gkdP[i] * ub_im);
+      g[2] += (double)(dSzP[i] * ua_re);
+      g[3] += (double)(dSaP[i] * ua_re);
     }
     __syncthreads();
   }
@@ -362,12 +366,19 @@ __global__ __launch_bounds__(512) void k_tf_grad_y(const DevOptics* __restrict__
   }
 }
 
-// Column tile of the gradient kernel: at most 512 threads (2 Y W <= 512 kEmax),
-// which leaves each thread the registers for its z-independent factors.
+// Column tile of the gradient kernel: two lateral frequencies per thread (and
+// four LDS elements), so that each thread keeps the z-independent factors of
+// its frequencies in registers; at most 1024 threads (Y W <= 2048).
 static int grad_tile_width(const Sampling& sm) {
   int W = 16;
-  while (W > 1 && 2L * W * sm.ny > 512L * kEmax) W /= 2;
+  while (W > 1 && (long)W * sm.ny > 2048) W /= 2;
   return W;
+}
+
+static int grad_threads(const Sampling& sm) {
+  long t = ((long)grad_tile_width(sm) * sm.ny + 1) / 2;
+  t = (t + 63) / 64 * 64;
+  return (int)(t < 64 ? 64 : t);
 }
 
 long grad_tiles(const Sampling& sm) {
@@ -377,18 +388,21 @@ long grad_tiles(const Sampling& sm) {
 
 // z chunk of the gradient kernel (the reduction reads ceil(nz / chunk) * tiles
 // partials per patch).
-int grad_z_chunk(const Sampling& sm, int nv) { return tf_z_chunk(sm, grad_tiles(sm), nv); }
+int grad_z_chunk(const Sampling& sm, int nv) {
+  // the pupil derivatives cost more than the planes' work: favour longer chunks
+  return tf_z_chunk(sm, grad_tiles(sm), nv, 512);
+}
 
 hipError_t launch_tf_grad_y(const DevOptics* opt, const Sampling& sm, int nv, const float2* ab,
                             double* gpart, double* ipart, hipStream_t s) {
   FftPlan plan;
   if (!make_plan(sm.ny, &plan)) return hipErrorInvalidValue;
-  if (2L * sm.ny > 512L * kEmax) return hipErrorInvalidValue;
+  if (sm.ny > 2048) return hipErrorInvalidValue;
   const int W = grad_tile_width(sm);
   const long tiles = grad_tiles(sm);
   const int ZC = grad_z_chunk(sm, nv);
   const long nwg = tiles * ((sm.nz + ZC - 1) / ZC) * (long)nv;
-  const int thr = threads_for((long)sm.ny * 2 * W);
+  const int thr = grad_threads(sm);
   const size_t lds = (size_t)(sm.ny + sm.ny * 2 * W) * sizeof(float2);
   ScopedTiming _t("k_tf_grad_y", s);
 #define X_(NN)                                                                                   \

@@ -167,16 +167,16 @@ __device__ __forceinline__ void fill_twiddles(float2* tw, int n, int tid, int nt
 // Cooperative copy of `total` (<= kEmax * nthr) elements into LDS, element e
 // taken from src(e).  Every load of a thread is issued before its LDS stores,
 // so the loads of one thread are in flight together.
-template <typename F>
+template <int EM = kEmax, typename F>
 __device__ __forceinline__ void gather_to_lds(float2* buf, int total, int tid, int nthr, F src) {
-  float2 t[kEmax];
+  float2 t[EM];
 #pragma unroll
-  for (int i = 0; i < kEmax; ++i) {
+  for (int i = 0; i < EM; ++i) {
     const int e = tid + i * nthr;
     if (e < total) t[i] = src(e);
   }
 #pragma unroll
-  for (int i = 0; i < kEmax; ++i) {
+  for (int i = 0; i < EM; ++i) {
     const int e = tid + i * nthr;
     if (e < total) buf[e] = t[i];
   }
@@ -434,11 +434,11 @@ struct StaticPlan {
   }
 };
 
-template <int N, int R, int NS, int NL, bool LF>
+template <int N, int R, int NS, int NL, bool LF, int EM>
 __device__ __forceinline__ void static_pass(float2* lds, int nl_rt, int es, int ls, int shift,
                                             const float2* tw, float s, int tid, int nthr) {
   constexpr int NB = N / R;
-  constexpr int BPT = (kEmax + R - 1) / R;
+  constexpr int BPT = (EM + R - 1) / R;
   constexpr int TWS = N / (NS * R);
   const int nl = NL > 0 ? NL : nl_rt;
   const int total = nl * NB;
@@ -484,22 +484,25 @@ __device__ __forceinline__ void static_pass(float2* lds, int nl_rt, int es, int 
   __syncthreads();
 }
 
-template <int N, int NL, bool LF, int Q = 0>
+template <int N, int NL, bool LF, int EM, int Q = 0>
 __device__ __forceinline__ void static_fft(float2* lds, int nl_rt, int es, int ls, int shift,
                                            const float2* tw, float s, int tid, int nthr) {
   if constexpr (Q < StaticPlan<N>::passes()) {
-    static_pass<N, StaticPlan<N>::radix(Q), StaticPlan<N>::span(Q), NL, LF>(lds, nl_rt, es, ls, shift,
-                                                                            tw, s, tid, nthr);
-    static_fft<N, NL, LF, Q + 1>(lds, nl_rt, es, ls, shift, tw, s, tid, nthr);
+    static_pass<N, StaticPlan<N>::radix(Q), StaticPlan<N>::span(Q), NL, LF, EM>(lds, nl_rt, es, ls,
+                                                                                shift, tw, s, tid, nthr);
+    static_fft<N, NL, LF, EM, Q + 1>(lds, nl_rt, es, ls, shift, tw, s, tid, nthr);
   }
 }
 
 // FFT of the lines described by L: static length NSTAT (> 0) or the runtime plan
 // (NSTAT == 0).  NL > 0 fixes the number of lines; LF must equal L.linefast.
-template <int NSTAT, int NL, bool LF>
+// EM bounds the elements a thread owns (lines * n <= threads * EM) for the
+// compiled stages; the runtime plan assumes kEmax.
+template <int NSTAT, int NL, bool LF, int EM = kEmax>
 __device__ __forceinline__ void fft_lines(float2* lds, const LdsLines& L, const FftPlan& p,
                                           const float2* tw, float s, int tid, int nthr) {
-  if constexpr (NSTAT > 0) static_fft<NSTAT, NL, LF>(lds, L.nl, L.es, L.ls, L.shift, tw, s, tid, nthr);
+  if constexpr (NSTAT > 0)
+    static_fft<NSTAT, NL, LF, EM>(lds, L.nl, L.es, L.ls, L.shift, tw, s, tid, nthr);
   else lds_fft(lds, L, p, tw, s, tid, nthr);
 }
 

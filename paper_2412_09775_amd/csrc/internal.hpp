@@ -117,7 +117,7 @@ hipError_t launch_set_params(DevOptics* dst, const DevOptics* host, int n, hipSt
 // ceil(nx / width) doubles per patch.
 int tf_tile_width(const Sampling& sm);
 // Planes per workgroup of the z-chunked field and gradient kernels.
-int tf_z_chunk(const Sampling& sm, long tiles_x, long npatch);
+int tf_z_chunk(const Sampling& sm, long tiles_x, long npatch, long target);
 hipError_t launch_tf_fields_y(const DevOptics* opt, const Sampling& sm, int npatch, float2* ab,
                               double* partials, hipStream_t s);
 hipError_t launch_tf_rows_labelfree(const double* partials, const Sampling& sm, int npatch,

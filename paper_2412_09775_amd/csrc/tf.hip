@@ -109,6 +109,7 @@ __global__ __launch_bounds__(1024) void k_tf_fields_y(const DevOptics* __restric
   constexpr int nf = NF;
   constexpr int EPT = kEmax / NF;   // elements of a thread: Y * W * NF <= threads * kEmax
   const int x0 = (int)(tile * W);
+  const int wsh = pow2_shift(W);     // W is a power of two
   // z-independent factors of this thread's elements e = tid + i * nthr
   double tkz[EPT], sp[EPT], gg[fluor ? 1 : EPT];
   {
@@ -125,7 +126,7 @@ __global__ __launch_bounds__(1024) void k_tf_fields_y(const DevOptics* __restric
       if (!fluor) gg[i] = 0.0;
       const int e = tid + i * nthr;
       if (e < Y * W) {
-        const int ky = e / W, w = e - ky * W;
+        const int ky = e >> wsh, w = e & (W - 1);
         const int kx = x0 + w;
         if (kx < X) {
           const double fy = fftfreq(ky, Y, sm.dy), fx = fftfreq(kx, X, sm.dx);
@@ -158,7 +159,7 @@ __global__ __launch_bounds__(1024) void k_tf_fields_y(const DevOptics* __restric
     for (int i = 0; i < EPT; ++i) {
       const int e = tid + i * nthr;
       if (e < Y * W) {
-        const int ky = e / W, w = e - ky * W;
+        const int ky = e >> wsh, w = e & (W - 1);
         float2 A = make_float2(0.f, 0.f), B = make_float2(0.f, 0.f);
         if (sp[i] != 0.0 || (!fluor && gg[i] != 0.0)) {
           // phase 2 pi kz (z - dz0): reduce the argument (in units of pi) in FP64
@@ -179,9 +180,9 @@ __global__ __launch_bounds__(1024) void k_tf_fields_y(const DevOptics* __restric
     fft_lines<NS, 0, true>(buf, LdsLines{nf * W, nf * W, 1, true, pow2_shift(nf * W)}, plan, tw, 1.f,
                            tid, nthr);
     scatter_from_lds(buf, Y * nf * W, tid, nthr, [&](int e, float2 v) {
-      const int ky = e / (nf * W);
-      const int r = e - ky * nf * W;
-      const int f = r / W, w = r - f * W;
+      const int ky = e >> (wsh + nf - 1);
+      const int r = e & (nf * W - 1);
+      const int f = r >> wsh, w = r & (W - 1);
       const int kx = x0 + w;
       if (kx < X) ab[(((patch * nf + f) * Z + z) * (long)Y + ky) * X + kx] = v;
     });
@@ -189,11 +190,11 @@ __global__ __launch_bounds__(1024) void k_tf_fields_y(const DevOptics* __restric
   }
 }
 
-// Planes per workgroup of the z-chunked kernels: enough workgroups to fill the
-// device (about 2048), at most 16 planes.
-int tf_z_chunk(const Sampling& sm, long tiles_x, long npatch) {
+// Planes per workgroup of the z-chunked kernels: about `target` workgroups
+// per launch, at most 16 planes.
+int tf_z_chunk(const Sampling& sm, long tiles_x, long npatch, long target) {
   const long wg_per_plane = tiles_x * npatch;
-  long zc = (long)sm.nz * wg_per_plane / 2048;
+  long zc = (long)sm.nz * wg_per_plane / target;
   if (zc < 1) zc = 1;
   if (zc > 16) zc = 16;
   if (zc > sm.nz) zc = sm.nz;
@@ -215,7 +216,7 @@ hipError_t launch_tf_fields_y(const DevOptics* opt, const Sampling& sm, int npat
   const int nf = sm.model == kFluor3D ? 1 : 2;
   const int W = tf_tile_width(sm);
   const long tiles = (sm.nx + W - 1) / W;
-  const int ZC = tf_z_chunk(sm, tiles, npatch);
+  const int ZC = tf_z_chunk(sm, tiles, npatch, 2048);
   const long nwg = tiles * ((sm.nz + ZC - 1) / ZC) * (long)npatch;
   const int thr = threads_for((long)sm.ny * nf * W);
   const size_t lds = (size_t)(sm.ny + sm.ny * nf * W) * sizeof(float2);
@@ -262,7 +263,9 @@ __global__ __launch_bounds__(1024) void k_tf_rows_lf(const double* __restrict__ 
                                                      long wg_per_patch, FftPlan plan) {
   __shared__ double ibg_s;
   extern __shared__ float2 smem[];
-  const int Y = sm.ny, X = sm.nx, Z = sm.nz, Xh = X / 2 + 1;
+  const int Y = sm.ny, Z = sm.nz;
+  const int X = NS > 0 ? NS : sm.nx;   // compile-time length for the index arithmetic
+  const int Xh = X / 2 + 1;
   float2* tw = smem;
   float2* buf = smem + X;
   const int tid = threadIdx.x, nthr = blockDim.x;
@@ -271,6 +274,7 @@ __global__ __launch_bounds__(1024) void k_tf_rows_lf(const double* __restrict__ 
   const long rpp = (long)Z * Y;
   const long row0 = (blockIdx.x - patch * wg_per_patch) * (long)rows_per_wg;
   const int nr = (int)min((long)rows_per_wg, rpp - row0);
+  const int z0 = (int)(row0 / Y), y0 = (int)(row0 - (long)z0 * Y);
   const float2* a_src = ab + (patch * 2 + 0) * rpp * X;
   const float2* b_src = ab + (patch * 2 + 1) * rpp * X;
   if (tid == 0) ibg_s = pupil_total(partials + patch * tiles_x, tiles_x);
@@ -296,12 +300,12 @@ __global__ __launch_bounds__(1024) void k_tf_rows_lf(const double* __restrict__ 
     const int r = e / Xh, k = e - r * Xh;
     const float2 Ck = buf[2 * r * X + k];
     const float2 Cm = buf[2 * r * X + (k == 0 ? 0 : X - k)];
-    const long row = row0 + r;
-    const long z = row / Y, y = row - z * Y;
+    int y = y0 + r, z = z0;
+    while (y >= Y) { y -= Y; ++z; }
     const float2 U = make_float2(Ck.x + Cm.x, Ck.y - Cm.y);          // C + conj(C(-k))
     const float2 V = make_float2(-(Ck.y + Cm.y), Ck.x - Cm.x);       // i (C - conj(C(-k)))
-    op[z * zstride + y * Xh + k] = U;
-    op[pstride + z * zstride + y * Xh + k] = V;
+    op[(long)z * zstride + (long)y * Xh + k] = U;
+    op[pstride + (long)z * zstride + (long)y * Xh + k] = V;
   }
 }
 
