@@ -60,33 +60,118 @@ def kernel_bytes(name, Z, Y, X, C=1, P=2):
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "labelfree3d_96x512x512_hbm_traffic.txt")
-COUNTED_SOURCES = [os.path.join(ROOT, "paper_2412_09775_amd", "csrc", f) for f in ("fft.hip", "common.hpp")]
-# kernel name in the library's timing report -> symbol prefix in the counter summary
-COUNTER_NAMES = {"k_zop<2>": "wo::k_zop<2, 1>", "k_rows_r2c": "wo::k_rows_r2c",
-                 "k_rows_c2r": "wo::k_rows_c2r", "k_tf_rows_lf": "wo::k_tf_rows_lf",
-                 "k_tf_fields_y": "wo::k_tf_fields_y"}
+CSRC = os.path.join(ROOT, "paper_2412_09775_amd", "csrc")
+# kernel name in the library's timing report -> symbol in the counter summary (the
+# column passes share one symbol across launches and are not listed)
+COUNTER_NAMES = {"k_zop<2>": "wo::k_zop<2, 1, 96>", "k_rows_r2c": "wo::k_rows_r2c<512>",
+                 "k_rows_c2r": "wo::k_rows_c2r<512>", "k_tf_rows_lf": "wo::k_tf_rows_lf<512>",
+                 "k_tf_fields_y": "wo::k_tf_fields_y<512, 2>"}
+
+
+def source_sha1():
+    """SHA-1 over every kernel source of the library (any change invalidates counters)."""
+    import hashlib
+    h = hashlib.sha1()
+    for f in sorted(os.listdir(CSRC)):
+        if f.endswith((".hip", ".hpp")):
+            h.update(f.encode())
+            h.update(open(os.path.join(CSRC, f), "rb").read())
+    return h.hexdigest()
 
 
 def measured_traffic(kernel):
     """HBM bytes per launch from the committed FETCH_SIZE/WRITE_SIZE summary, or None
     when the kernel sources changed since the counters were taken."""
-    import hashlib
     try:
         lines = open(TRAFFIC_FILE).read().splitlines()
     except OSError:
         return None
-    sha = hashlib.sha1(b"".join(open(p, "rb").read() for p in COUNTED_SOURCES)).hexdigest()
     rec = [ln.split()[1] for ln in lines if ln.startswith("source_sha1")]
-    if not rec or rec[0] != sha or kernel not in COUNTER_NAMES:
+    if not rec or rec[0] != source_sha1() or kernel not in COUNTER_NAMES:
         return None
     want = COUNTER_NAMES[kernel]
     best = None
     for ln in lines:
-        if ln.startswith(want):
-            parts = ln[len(want):].split()
-            mb = float(parts[-1])
+        f = ln.split("\t")
+        if len(f) >= 5 and f[0] == want:
+            mb = float(f[-1])
             best = mb if best is None else max(best, mb)   # the largest dispatch is the workload's
     return None if best is None else int(best * 1e6)
+
+
+def _symbol(name):
+    name = name[5:] if name.startswith("void ") else name
+    return name.split("(")[0]
+
+
+def summarise_trace(trace_dir, command):
+    """Per (kernel, grid) call count and average duration from a rocprofv3
+    --kernel-trace CSV directory, as the text committed under profiles/."""
+    import csv
+    import glob
+    path = glob.glob(os.path.join(trace_dir, "*kernel_trace.csv"))[0]
+    agg = {}
+    for r in csv.DictReader(open(path)):
+        k = (_symbol(r["Kernel_Name"]), int(r["Grid_Size_X"]))
+        d = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-3
+        c, t = agg.get(k, (0, 0.0))
+        agg[k] = (c + 1, t + d)
+    out = ["# Kernel durations: label-free 3D, 96x512x512, 1 channel x 2 properties "
+           "(TF synthesis + reconstruction)",
+           f"# command: {command}",
+           f"source_sha1 {source_sha1()}",
+           "kernel\tgrid\tcalls\tavg_us\ttotal_us"]
+    for (k, g), (c, t) in sorted(agg.items(), key=lambda kv: -kv[1][1]):
+        out.append(f"{k}\t{g}\t{c}\t{t / c:.1f}\t{t:.1f}")
+    return "\n".join(out) + "\n"
+
+
+def summarise_counters(fetch_dir, write_dir, commands):
+    """Per-dispatch FETCH_SIZE and WRITE_SIZE (KiB) of every kernel, scaled by what the
+    counters read for the 1 GiB device copy in the same run, in MB per dispatch."""
+    import csv
+    import glob
+
+    def load(d, counter):
+        path = glob.glob(os.path.join(d, "*counter_collection.csv"))[0]
+        rows = {}
+        for r in csv.DictReader(open(path)):
+            if r["Counter_Name"] == counter:
+                rows[int(r["Dispatch_Id"])] = (_symbol(r["Kernel_Name"]), int(r["Grid_Size"]),
+                                               float(r["Counter_Value"]))
+        return rows
+
+    fe, wr = load(fetch_dir, "FETCH_SIZE"), load(write_dir, "WRITE_SIZE")
+    gib = 1 << 30
+    copies_f = [v for v in fe.values() if "copyBuffer" in v[0] and v[2] > 0.25 * gib / 1024]
+    copies_w = [v for v in wr.values() if "copyBuffer" in v[0] and v[2] > 0.25 * gib / 1024]
+    cf = max(v[2] for v in copies_f) if copies_f else 0.0
+    cw = max(v[2] for v in copies_w) if copies_w else 0.0
+    sf = (gib / 1024) / cf if cf else 1.0
+    sw = (gib / 1024) / cw if cw else 1.0
+    # dispatch ids differ between the two runs: pair the n-th dispatch of each (kernel, grid)
+    from collections import defaultdict
+    seq_f, seq_w = defaultdict(list), defaultdict(list)
+    for i in sorted(fe):
+        seq_f[fe[i][:2]].append(fe[i][2])
+    for i in sorted(wr):
+        seq_w[wr[i][:2]].append(wr[i][2])
+    out = ["# HBM traffic per dispatch: label-free 3D, 96x512x512 (same workload as the kernel "
+           "durations)"]
+    out += [f"# command: {c}" for c in commands]
+    out += [f"# calibration: 1 GiB device copy reads FETCH_SIZE={cf:.1f} KiB, "
+            f"WRITE_SIZE={cw:.1f} KiB",
+            f"# scale factors: fetch x{sf:.3f}, write x{sw:.3f}",
+            f"source_sha1 {source_sha1()}",
+            "kernel\tgrid\tFETCH_KiB\tWRITE_KiB\tscaled_MB"]
+    for key in sorted(set(seq_f) & set(seq_w)):
+        if "copyBuffer" in key[0] or key[0].startswith("at::") or "elementwise" in key[0]:
+            continue
+        f = sum(seq_f[key]) / len(seq_f[key])
+        w = sum(seq_w[key]) / len(seq_w[key])
+        mb = (f * sf + w * sw) * 1024 / 1e6
+        out.append(f"{key[0]}\t{key[1]}\t{f:.1f}\t{w:.1f}\t{mb:.1f}")
+    return "\n".join(out) + "\n"
 
 
 def main():
@@ -109,7 +194,23 @@ def main():
     ap.add_argument("--restore-graph", type=int, default=1, choices=(0, 1, 2))
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for HBM counters)")
+    ap.add_argument("--summarise-trace", default="", help="(no GPU) write the kernel-duration "
+                    "summary of a rocprofv3 --kernel-trace directory to --summary-out")
+    ap.add_argument("--summarise-counters", nargs=2, default=None, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="(no GPU) write the FETCH_SIZE/WRITE_SIZE summary to --summary-out")
+    ap.add_argument("--summary-command", action="append", default=[],
+                    help="command line recorded in the summary header (repeatable)")
+    ap.add_argument("--summary-out", default="")
     args = ap.parse_args()
+    if args.summarise_trace or args.summarise_counters:
+        text = (summarise_trace(args.summarise_trace, " ".join(args.summary_command))
+                if args.summarise_trace else
+                summarise_counters(*args.summarise_counters, args.summary_command))
+        if args.summary_out:
+            open(args.summary_out, "w").write(text)
+        else:
+            sys.stdout.write(text)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus above 1 is not supported"}))
         sys.exit(2)
