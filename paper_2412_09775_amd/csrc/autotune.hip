@@ -66,6 +66,7 @@ __global__ __launch_bounds__(256) void k_loss_grad(const DevOptics* __restrict__
     // pass 1: normal matrix and right-hand side
     float m00 = 0.f, m11 = 0.f;
     float2 m10 = make_float2(0.f, 0.f), r0 = make_float2(0.f, 0.f), r1 = make_float2(0.f, 0.f);
+#pragma unroll 4
     for (int c = 0; c < Z; ++c) {
       const float2 h0 = hp[(long)(2 * c) * M], h1 = hp[(long)(2 * c + 1) * M];
       const float2 x = dp[(long)c * M];
@@ -88,6 +89,7 @@ __global__ __launch_bounds__(256) void k_loss_grad(const DevOptics* __restrict__
       const float2 g0 = cscale(F0, -ib);                  // dL/dF_phase*
       const float2 Y0 = cscale(cscale(g0, a11), idet);    // Y = M^-1 (g0, 0)
       const float2 Y1 = cscale(cmul(m10, g0), -idet);
+#pragma unroll 4
       for (int c = 0; c < Z; ++c) {
         const float2 h0 = hp[(long)(2 * c) * M], h1 = hp[(long)(2 * c + 1) * M];
         const float2 x = dp[(long)c * M];
@@ -155,35 +157,43 @@ __global__ __launch_bounds__(1024) void k_tf_rows_bwd(const double* __restrict__
     for (long i = 0; i < tiles_x; ++i) t += partials[v * tiles_x + i];
     ibg_s = t;
   }
-  gather_to_lds(buf, nr * 2 * X, tid, nthr, [&](int e) {
+  const int LS = row_stride(X);      // padded line pitch in LDS
+  auto slot = [&](int e) {           // line 2r: a (then u_A), line 2r + 1: b (then u_B)
+    const int t = e / X;
+    return t * LS + row_slot(e - t * X);
+  };
+  gather_to_lds_map(buf, nr * 2 * X, tid, nthr, [&](int e) {
     const int i = e % X;
     const int t = e / X;
     const int f = t & 1, r = t >> 1;
     const float2* src = f ? b_src : a_src;
     return src[(row0 + r) * X + i];
-  });
+  }, slot, [] {});
   __syncthreads();
-  fft_lines<NS, 0, false>(buf, LdsLines{2 * nr, 1, X, false}, plan, tw, 1.f, tid, nthr);
+  fft_lines<NS, 0, false, kEmax, true>(buf, LdsLines{2 * nr, 1, LS, false, -1, true}, plan, tw, 1.f,
+                                       tid, nthr);
   const float k = (float)(1.0 / ((double)X * (double)Y * ibg_s));
   double dsum = 0.0;
   for (int e = tid; e < nr * X; e += nthr) {
     const int r = e / X, i = e - r * X;
+    const int si = row_slot(i);
     int y = y0 + r, z = z0;
     while (y >= Y) { y -= Y; ++z; }
     const float gph = gam[(((v * Z + z) * 2 + 0) * (long)Y + y) * X + i];
     const float gab = gam[(((v * Z + z) * 2 + 1) * (long)Y + y) * X + i];
     const float2 G = make_float2(gph, gab);
-    const float2 a = buf[2 * r * X + i], b = buf[(2 * r + 1) * X + i];
+    const float2 a = buf[2 * r * LS + si], b = buf[(2 * r + 1) * LS + si];
     const float2 gb = cmul(G, b);
     dsum += (double)gb.x * a.x + (double)gb.y * a.y;     // Re(G b conj(a))
-    buf[2 * r * X + i] = cscale(cconj(gb), k);          // u_A
-    buf[(2 * r + 1) * X + i] = cscale(cmulconj(G, a), k);  // u_B
+    buf[2 * r * LS + si] = cscale(cconj(gb), k);          // u_A
+    buf[(2 * r + 1) * LS + si] = cscale(cmulconj(G, a), k);  // u_B
   }
   const double tot = block_sum_d(dsum, red);
   if (tid == 0) dpart[v * wg_per_patch + wg] = tot;
   __syncthreads();
-  fft_lines<NS, 0, false>(buf, LdsLines{2 * nr, 1, X, false}, plan, tw, 1.f, tid, nthr);
-  scatter_from_lds(buf, nr * 2 * X, tid, nthr, [&](int e, float2 val) {
+  fft_lines<NS, 0, false, kEmax, true>(buf, LdsLines{2 * nr, 1, LS, false, -1, true}, plan, tw, 1.f,
+                                       tid, nthr);
+  scatter_from_lds_map(buf, nr * 2 * X, tid, nthr, slot, [&](int e, float2 val) {
     const int i = e % X;
     const int t = e / X;
     const int f = t & 1, r = t >> 1;
@@ -212,7 +222,7 @@ hipError_t launch_tf_rows_bwd(const double* partials, const Sampling& sm, int nv
   const long wpp = bwd_wg_per_patch(sm);
   const long tiles_x = (sm.nx + tf_tile_width(sm) - 1) / tf_tile_width(sm);
   const int thr = threads_for(2L * R * sm.nx);
-  const size_t lds = (size_t)(sm.nx + 2 * R * sm.nx) * sizeof(float2);
+  const size_t lds = (size_t)(sm.nx + 2L * R * row_stride(sm.nx)) * sizeof(float2);
   ScopedTiming _t("k_tf_rows_bwd", s);
 #define X_(NN)                                                                                   \
   case NN:                                                                                       \

@@ -201,6 +201,41 @@ __device__ __forceinline__ void gather_to_lds(float2* buf, int total, int tid, i
   }
 }
 
+// As gather_to_lds, element e stored at buf[slot(e)].
+template <typename F, typename S, typename G>
+__device__ __forceinline__ void gather_to_lds_map(float2* buf, int total, int tid, int nthr, F src,
+                                                  S slot, G mid) {
+  float2 t[kEmax];
+#pragma unroll
+  for (int i = 0; i < kEmax; ++i) {
+    const int e = tid + i * nthr;
+    if (e < total) t[i] = src(e);
+  }
+  mid();
+#pragma unroll
+  for (int i = 0; i < kEmax; ++i) {
+    const int e = tid + i * nthr;
+    if (e < total) buf[slot(e)] = t[i];
+  }
+}
+
+// As scatter_from_lds, element e read from buf[slot(e)].
+template <typename F, typename S>
+__device__ __forceinline__ void scatter_from_lds_map(const float2* buf, int total, int tid, int nthr,
+                                                     S slot, F dst) {
+  float2 t[kEmax];
+#pragma unroll
+  for (int i = 0; i < kEmax; ++i) {
+    const int e = tid + i * nthr;
+    if (e < total) t[i] = buf[slot(e)];
+  }
+#pragma unroll
+  for (int i = 0; i < kEmax; ++i) {
+    const int e = tid + i * nthr;
+    if (e < total) dst(e, t[i]);
+  }
+}
+
 // Cooperative write-out of `total` (<= kEmax * nthr) elements: dst(e, value).
 template <typename F>
 __device__ __forceinline__ void scatter_from_lds(const float2* buf, int total, int tid, int nthr,
@@ -228,7 +263,16 @@ struct LdsLines {
   int ls;     // line stride
   bool linefast;
   int shift = -1;   // log2(nl) when nl is a power of two (slot -> line by masks), else -1
+  bool pad = false; // row layout with one padding slot after every 8 elements (see row_slot)
 };
+
+// Row layout (lines contiguous in LDS): element i of a line sits at
+// row_slot(i) = i + i / 8.  A Stockham pass writes its first outputs with a
+// stride of R elements; the padding turns that stride into R + R/8, which
+// spreads the 64 lanes of a write over the LDS banks.  row_stride(n) is the
+// line pitch that holds n padded elements.
+__host__ __device__ __forceinline__ int row_slot(int i) { return i + (i >> 3); }
+__host__ __device__ __forceinline__ int row_stride(int n) { return n + (n >> 3) + 1; }
 
 // log2(n) for a power of two n, else -1.
 __host__ __device__ inline int pow2_shift(int n) {
@@ -263,7 +307,8 @@ __device__ __forceinline__ void stockham_pass(float2* lds, const LdsLines L, int
       kk[b] = k;
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        float2 x = lds[lb + (k + r * nb) * L.es];
+        const int idx = k + r * nb;
+        float2 x = lds[lb + (L.pad ? row_slot(idx) : idx * L.es)];
         if (r > 0) {
           float2 w = tw[r * km * twstep];
           if (s > 0.f) w.y = -w.y;
@@ -281,7 +326,10 @@ __device__ __forceinline__ void stockham_pass(float2* lds, const LdsLines L, int
       const int k = kk[b];
       const int d0 = (k / ns) * ns * R + (k % ns);
 #pragma unroll
-      for (int r = 0; r < R; ++r) lds[base[b] + (d0 + r * ns) * L.es] = v[b][r];
+      for (int r = 0; r < R; ++r) {
+        const int idx = d0 + r * ns;
+        lds[base[b] + (L.pad ? row_slot(idx) : idx * L.es)] = v[b][r];
+      }
     }
   }
   __syncthreads();
@@ -434,7 +482,7 @@ struct StaticPlan {
   }
 };
 
-template <int N, int R, int NS, int NL, bool LF, int EM>
+template <int N, int R, int NS, int NL, bool LF, int EM, bool PD>
 __device__ __forceinline__ void static_pass(float2* lds, int nl_rt, int es, int ls, int shift,
                                             const float2* tw, float s, int tid, int nthr) {
   constexpr int NB = N / R;
@@ -460,7 +508,8 @@ __device__ __forceinline__ void static_pass(float2* lds, int nl_rt, int es, int 
       kk[b] = k;
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        float2 x = lds[lb + (k + r * NB) * es];
+        const int idx = k + r * NB;
+        float2 x = lds[lb + (PD ? row_slot(idx) : idx * es)];
         if (r > 0) {
           float2 w = tw[r * km * TWS];
           if (s > 0.f) w.y = -w.y;
@@ -478,19 +527,22 @@ __device__ __forceinline__ void static_pass(float2* lds, int nl_rt, int es, int 
       const int k = kk[b];
       const int d0 = (k / NS) * NS * R + (k % NS);
 #pragma unroll
-      for (int r = 0; r < R; ++r) lds[base[b] + (d0 + r * NS) * es] = v[b][r];
+      for (int r = 0; r < R; ++r) {
+        const int idx = d0 + r * NS;
+        lds[base[b] + (PD ? row_slot(idx) : idx * es)] = v[b][r];
+      }
     }
   }
   __syncthreads();
 }
 
-template <int N, int NL, bool LF, int EM, int Q = 0>
+template <int N, int NL, bool LF, int EM, bool PD, int Q = 0>
 __device__ __forceinline__ void static_fft(float2* lds, int nl_rt, int es, int ls, int shift,
                                            const float2* tw, float s, int tid, int nthr) {
   if constexpr (Q < StaticPlan<N>::passes()) {
-    static_pass<N, StaticPlan<N>::radix(Q), StaticPlan<N>::span(Q), NL, LF, EM>(lds, nl_rt, es, ls,
-                                                                                shift, tw, s, tid, nthr);
-    static_fft<N, NL, LF, EM, Q + 1>(lds, nl_rt, es, ls, shift, tw, s, tid, nthr);
+    static_pass<N, StaticPlan<N>::radix(Q), StaticPlan<N>::span(Q), NL, LF, EM, PD>(
+        lds, nl_rt, es, ls, shift, tw, s, tid, nthr);
+    static_fft<N, NL, LF, EM, PD, Q + 1>(lds, nl_rt, es, ls, shift, tw, s, tid, nthr);
   }
 }
 
@@ -498,12 +550,14 @@ __device__ __forceinline__ void static_fft(float2* lds, int nl_rt, int es, int l
 // (NSTAT == 0).  NL > 0 fixes the number of lines; LF must equal L.linefast.
 // EM bounds the elements a thread owns (lines * n <= threads * EM) for the
 // compiled stages; the runtime plan assumes kEmax.
-template <int NSTAT, int NL, bool LF, int EM = kEmax>
+// PD must equal L.pad (the padded row layout).
+template <int NSTAT, int NL, bool LF, int EM = kEmax, bool PD = false>
 __device__ __forceinline__ void fft_lines(float2* lds, const LdsLines& L, const FftPlan& p,
                                           const float2* tw, float s, int tid, int nthr) {
   if constexpr (NSTAT > 0)
-    static_fft<NSTAT, NL, LF, EM>(lds, L.nl, L.es, L.ls, L.shift, tw, s, tid, nthr);
-  else lds_fft(lds, L, p, tw, s, tid, nthr);
+    static_fft<NSTAT, NL, LF, EM, PD>(lds, L.nl, L.es, L.ls, L.shift, tw, s, tid, nthr);
+  else
+    lds_fft(lds, L, p, tw, s, tid, nthr);
 }
 
 }  // namespace wo

@@ -36,22 +36,27 @@ __global__ __launch_bounds__(1024) void k_rows_r2c(const float* __restrict__ in,
   }
   __syncthreads();
   const int Xc = NS > 0 ? NS : X;   // compile-time length for the index arithmetic
-  gather_to_lds(buf, nl * Xc, tid, nthr, [&](int e) {
+  const int LS = row_stride(Xc);    // padded line pitch in LDS
+  gather_to_lds_map(buf, nl * Xc, tid, nthr, [&](int e) {
     const int l = e / Xc, i = e - l * Xc;
     const float a = in[rin[2 * l] * X + i];
     const float b = rin[2 * l + 1] >= 0 ? in[rin[2 * l + 1] * X + i] : 0.f;
     return make_float2(a, b);
+  }, [&](int e) {
+    const int l = e / Xc;
+    return l * LS + row_slot(e - l * Xc);
   }, [&] { fill_twiddles(tw, X, tid, nthr); });
   __syncthreads();
-  fft_lines<NS, 0, false>(buf, LdsLines{nl, 1, X, false}, plan, tw, -1.f, tid, nthr);
+  fft_lines<NS, 0, false, kEmax, true>(buf, LdsLines{nl, 1, LS, false, -1, true}, plan, tw, -1.f, tid,
+                                       nthr);
   const int Xh = Xc / 2 + 1;
 #pragma unroll
   for (int i = 0; i < kEmax; ++i) {
     const int e = tid + i * nthr;
     if (e < nl * Xh) {
       const int l = e / Xh, k = e - l * Xh;
-      const float2 zk = buf[l * Xc + k];
-      const float2 zm = buf[l * Xc + (k == 0 ? 0 : Xc - k)];
+      const float2 zk = buf[l * LS + row_slot(k)];
+      const float2 zm = buf[l * LS + row_slot(k == 0 ? 0 : Xc - k)];
       const float2 A = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y));
       const float2 B = make_float2(0.5f * (zk.y + zm.y), -0.5f * (zk.x - zm.x));
       out[rout[2 * l] * Xh + k] = A;
@@ -81,7 +86,12 @@ __global__ __launch_bounds__(1024) void k_rows_c2r(const float2* __restrict__ in
   __syncthreads();
   const int Xc = NS > 0 ? NS : X;   // compile-time length for the index arithmetic
   const int Xh = Xc / 2 + 1;
-  gather_to_lds(buf, nl * Xc, tid, nthr, [&](int e) {
+  const int LS = row_stride(Xc);    // padded line pitch in LDS
+  auto slot = [&](int e) {
+    const int l = e / Xc;
+    return l * LS + row_slot(e - l * Xc);
+  };
+  gather_to_lds_map(buf, nl * Xc, tid, nthr, [&](int e) {
     const int l = e / Xc, k = e - l * Xc;
     const bool mirror = 2 * k > Xc;
     const int kk = mirror ? Xc - k : k;
@@ -90,10 +100,11 @@ __global__ __launch_bounds__(1024) void k_rows_c2r(const float2* __restrict__ in
     if (kk == 0 || 2 * kk == Xc) { A.y = 0.f; B.y = 0.f; }   // Re of the inverse ignores them
     if (mirror) { A.y = -A.y; B.y = -B.y; }
     return make_float2(A.x - B.y, A.y + B.x);
-  }, [&] { fill_twiddles(tw, X, tid, nthr); });
+  }, slot, [&] { fill_twiddles(tw, X, tid, nthr); });
   __syncthreads();
-  fft_lines<NS, 0, false>(buf, LdsLines{nl, 1, X, false}, plan, tw, 1.f, tid, nthr);
-  scatter_from_lds(buf, nl * Xc, tid, nthr, [&](int e, float2 v) {
+  fft_lines<NS, 0, false, kEmax, true>(buf, LdsLines{nl, 1, LS, false, -1, true}, plan, tw, 1.f, tid,
+                                       nthr);
+  scatter_from_lds_map(buf, nl * Xc, tid, nthr, slot, [&](int e, float2 v) {
     const int l = e / Xc, i = e - l * Xc;
     out[rout[2 * l] * X + i] = v.x * scale;
     if (rout[2 * l + 1] >= 0) out[rout[2 * l + 1] * X + i] = v.y * scale;
@@ -127,7 +138,8 @@ static bool threads_ok(int thr, long elems) {
 static bool rows_choice_ok(int X, const FftChoice& c) {
   const long elems = (long)c.w * X;
   return c.w >= 1 && c.w <= 64 && elems <= kMaxElems && threads_ok(c.threads, elems) &&
-         (long)(X + elems) * (long)sizeof(float2) <= lds_limit_bytes() && c.plan >= 0 && c.plan <= 3;
+         (long)(X + (long)c.w * row_stride(X)) * (long)sizeof(float2) <= lds_limit_bytes() &&
+         c.plan >= 0 && c.plan <= 3;
 }
 
 static FftChoice rows_default(int X) {
@@ -159,7 +171,7 @@ hipError_t launch_rows_r2c(const float* in, float2* out, int X, const RowGroups&
   const int L = c.w;
   const long nwg = (nlines + L - 1) / L;
   const int thr = c.threads;
-  const size_t lds = (size_t)(X + L * X) * sizeof(float2);
+  const size_t lds = (size_t)(X + (long)L * row_stride(X)) * sizeof(float2);
   ScopedTiming _t("k_rows_r2c", s);
 #define WO_ROWS_ARGS in, out, X, g, plan, L, nlines
 #define X_(NN) WO_CASE_ROWS(k_rows_r2c, NN)
@@ -186,7 +198,7 @@ hipError_t launch_rows_c2r(const float2* in, float* out, int X, const RowGroups&
   const int L = c.w;
   const long nwg = (nlines + L - 1) / L;
   const int thr = c.threads;
-  const size_t lds = (size_t)(X + L * X) * sizeof(float2);
+  const size_t lds = (size_t)(X + (long)L * row_stride(X)) * sizeof(float2);
   ScopedTiming _t("k_rows_c2r", s);
 #define WO_ROWS_ARGS in, out, X, g, plan, L, nlines, scale
 #define X_(NN) WO_CASE_ROWS(k_rows_c2r, NN)

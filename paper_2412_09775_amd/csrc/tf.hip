@@ -278,28 +278,35 @@ __global__ __launch_bounds__(1024) void k_tf_rows_lf(const double* __restrict__ 
   const float2* a_src = ab + (patch * 2 + 0) * rpp * X;
   const float2* b_src = ab + (patch * 2 + 1) * rpp * X;
   if (tid == 0) ibg_s = pupil_total(partials + patch * tiles_x, tiles_x);
-  gather_to_lds(buf, nr * 2 * X, tid, nthr, [&](int e) {
+  const int LS = row_stride(X);      // padded line pitch in LDS
+  // line 2r holds a, line 2r + 1 holds b of row r
+  gather_to_lds_map(buf, nr * 2 * X, tid, nthr, [&](int e) {
     const int i = e % X;
     const int t = e / X;
     const int f = t & 1, r = t >> 1;
     const float2* src = f ? b_src : a_src;
     return src[(row0 + r) * X + i];
-  });
+  }, [&](int e) {
+    const int t = e / X;
+    return t * LS + row_slot(e - t * X);
+  }, [] {});
   __syncthreads();
-  fft_lines<NS, 0, false>(buf, LdsLines{2 * nr, 1, X, false}, plan, tw, 1.f, tid, nthr);
+  fft_lines<NS, 0, false, kEmax, true>(buf, LdsLines{2 * nr, 1, LS, false, -1, true}, plan, tw, 1.f,
+                                       tid, nthr);
   const float cs = (float)(1.0 / ((double)X * (double)Y * ibg_s));
   for (int e = tid; e < nr * X; e += nthr) {
-    const int r = e / X, i = e - r * X;
-    const float2 a = buf[2 * r * X + i], b = buf[(2 * r + 1) * X + i];
-    buf[2 * r * X + i] = cscale(cmulconj(b, a), cs);
+    const int r = e / X, i = row_slot(e - r * X);
+    const float2 a = buf[2 * r * LS + i], b = buf[(2 * r + 1) * LS + i];
+    buf[2 * r * LS + i] = cscale(cmulconj(b, a), cs);
   }
   __syncthreads();
-  fft_lines<NS, 0, false>(buf, LdsLines{nr, 1, 2 * X, false}, plan, tw, -1.f, tid, nthr);
+  fft_lines<NS, 0, false, kEmax, true>(buf, LdsLines{nr, 1, 2 * LS, false, -1, true}, plan, tw, -1.f,
+                                       tid, nthr);
   float2* op = out + patch * patch_stride;
   for (int e = tid; e < nr * Xh; e += nthr) {
     const int r = e / Xh, k = e - r * Xh;
-    const float2 Ck = buf[2 * r * X + k];
-    const float2 Cm = buf[2 * r * X + (k == 0 ? 0 : X - k)];
+    const float2 Ck = buf[2 * r * LS + row_slot(k)];
+    const float2 Cm = buf[2 * r * LS + row_slot(k == 0 ? 0 : X - k)];
     int y = y0 + r, z = z0;
     while (y >= Y) { y -= Y; ++z; }
     const float2 U = make_float2(Ck.x + Cm.x, Ck.y - Cm.y);          // C + conj(C(-k))
@@ -322,7 +329,7 @@ hipError_t launch_tf_rows_labelfree(const double* partials, const Sampling& sm, 
   const long wpp = (rpp + R - 1) / R;
   const long nwg = wpp * npatch;
   const int thr = threads_for(2L * R * sm.nx);
-  const size_t lds = (size_t)(sm.nx + 2 * R * sm.nx) * sizeof(float2);
+  const size_t lds = (size_t)(sm.nx + 2L * R * row_stride(sm.nx)) * sizeof(float2);
   ScopedTiming _t("k_tf_rows_lf", s);
 #define X_(NN)                                                                                   \
   case NN:                                                                                       \
