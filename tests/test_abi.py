@@ -81,6 +81,13 @@ def test_null_and_small_workspace_are_rejected(lib):
                               ctypes.c_void_p(1), ctypes.c_void_p(1), 1 << 40, None) == -1
     assert lib.wo_reconstruct(arr, 1, ctypes.c_void_p(1), ctypes.c_void_p(1), None, 0.0,
                               ctypes.c_void_p(1), ctypes.c_void_p(1), 1 << 40, None) == -2
+    # an empty batch is rejected, not treated as a no-op
+    assert lib.wo_transfer_function(arr, 0, ctypes.c_void_p(1), ctypes.c_void_p(1), 1 << 40, None) == -1
+    assert lib.wo_reconstruct(arr, 0, ctypes.c_void_p(1), ctypes.c_void_p(1), None, 1e-3,
+                              ctypes.c_void_p(1), ctypes.c_void_p(1), 1 << 40, None) == -1
+    assert lib.wo_tune_workspace_size(arr, 0, 1) == 0
+    big = api.optics_array(_optics(nx=8192))        # beyond the 4096 limit
+    assert lib.wo_transfer_function(big, 1, ctypes.c_void_p(1), ctypes.c_void_p(1), 1 << 40, None) == -2
     mixed = api.optics_array([_optics(), _optics(nz=16)])
     assert lib.wo_forward(mixed, 2, ctypes.c_void_p(1), ctypes.c_void_p(1), None,
                           ctypes.c_void_p(1), ctypes.c_void_p(1), 1 << 40, None) == -1

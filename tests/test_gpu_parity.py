@@ -69,6 +69,14 @@ CASES = {
     "thin_batch3": [thin(defocus=0.4, na_det=1.05, tilt_zenith=0.2),
                     thin(defocus=-1.1, na_det=1.25, tilt_zenith=0.45, tilt_azimuth=0.3),
                     thin(defocus=0.0, na_det=1.15)],
+    # degenerate and extreme cases: coherent point source (NA_ill = 0) with odd Z and
+    # lengths without compiled stages; the smallest volume; the longest rows and the
+    # deepest stack the ABI accepts (4096, runtime plans, one column per Z tile)
+    "labelfree_coherent_odd": [labelfree(nz=9, ny=40, nx=50, na_ill=0.0, defocus=0.1)],
+    "labelfree_tiny": [labelfree(nz=2, ny=8, nx=8)],
+    "labelfree_rows_4096": [labelfree(nz=2, ny=8, nx=4096)],
+    "fluor_depth_4096": [fluor(nz=4096, ny=8, nx=8, dz=0.25)],
+    "pol5_ragged": [pol5(nz=12, ny=40, nx=50, tilt_zenith=0.1)],
 }
 
 
