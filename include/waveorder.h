@@ -152,7 +152,7 @@ int wo_adjoint(const wo_optics* o, int32_t n, const void* tf, const float* r, fl
  * are needed for non-zero NA and tilt gradients. */
 
 /* Unlike the calls above, the calls of this section accept patches of uneven
- * shapes (each o[i] its own nz >= 2, ny <= 2048, nx, dz, dy, dx): the stacks are
+ * shapes (each o[i] its own nz >= 2, ny and nx <= 2048, dz, dy, dx): the stacks are
  * packed, patch i's [nz_i][ny_i][nx_i] floats following patch i-1's, and the
  * patches that share a sampling are processed by the same launches
  * (shift-variant processing of overlapping tiles, Methods "Cell-scale optical

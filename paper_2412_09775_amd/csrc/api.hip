@@ -285,7 +285,7 @@ int run_linear(const wo_optics* o, int32_t n, const Shape& s, const float2* tf, 
 struct TuneLayout {
   int np, nv;
   long tiles, lbpp, dwpp;
-  size_t off_opt, off_st, off_D, off_bank, off_ab, off_gam, off_pp, off_lp, off_dp, off_gp, off_ip,
+  size_t off_opt, off_st, off_D, off_bank, off_ab, off_pp, off_lp, off_dp, off_gp, off_ip,
       off_ropt, off_reta, total;
 };
 
@@ -306,7 +306,6 @@ TuneLayout tune_layout(const wo_optics* o, int32_t n, int32_t starts) {
   L.off_D = take((size_t)n * Z * Y * Xh * sizeof(float2));
   L.off_bank = take((size_t)L.nv * 2 * Z * Y * Xh * sizeof(float2));
   L.off_ab = take((size_t)L.nv * 2 * Z * Y * X * sizeof(float2));
-  L.off_gam = take((size_t)L.nv * 2 * Z * Y * X * sizeof(float));
   L.off_pp = take((size_t)L.nv * L.tiles * sizeof(double));
   L.off_lp = take((size_t)L.nv * L.lbpp * sizeof(double));
   L.off_dp = take((size_t)L.nv * L.dwpp * sizeof(double));
@@ -420,7 +419,6 @@ int tune_iteration(const TuneGroup& g, char* ws, int starts, int update, hipStre
   float2* D = (float2*)(w + L.off_D);
   float2* bank = (float2*)(w + L.off_bank);
   float2* ab = (float2*)(w + L.off_ab);
-  float* gam = (float*)(w + L.off_gam);
   double* pp = (double*)(w + L.off_pp);
   double* lp = (double*)(w + L.off_lp);
   double* dp = (double*)(w + L.off_dp);
@@ -432,9 +430,7 @@ int tune_iteration(const TuneGroup& g, char* ws, int starts, int update, hipStre
   WO_TRY(launch_cols(bank, (int)Y, Xh, 2 * Z, 2 * Z, nv, -1.f, hs, "k_cols_y_tf"));
   WO_TRY(launch_loss_grad(dopt, st, sm, nv, D, bank, lp, starts, hs));
   WO_TRY(launch_cols(bank, (int)Y, Xh, 2 * Z, 2 * Z, nv, 1.f, hs, "k_cols_y_grad"));
-  RowGroups rg{2 * Z * Y, 2 * Z * Y, 2 * Z * Y, nv};
-  WO_TRY(launch_rows_c2r(bank, gam, sm.nx, rg, 1.f, hs));
-  WO_TRY(launch_tf_rows_bwd(pp, sm, nv, ab, gam, dp, hs));
+  WO_TRY(launch_tf_rows_bwd(pp, sm, nv, ab, bank, dp, hs));
   WO_TRY(launch_tf_grad_y(dopt, sm, nv, ab, gp, ip, hs));
   WO_TRY(launch_adam(dopt, st, sm, nv, pp, lp, dp, gp, ip, update, hs));
   return WO_OK;
@@ -480,7 +476,7 @@ int validate_thin(const wo_optics* o, int32_t n) {
   for (int i = 0; i < n; ++i) {
     int st = check_sampling(&o[i]);
     if (st) return st;
-    if (o[i].model != WO_MODEL_LABELFREE_THIN || o[i].nz < 2 || o[i].ny > 2048)
+    if (o[i].model != WO_MODEL_LABELFREE_THIN || o[i].nz < 2 || o[i].ny > 2048 || o[i].nx > 2048)
       return WO_EUNSUPPORTED;
     st = check_optics(&o[i]);
     if (st) return st;

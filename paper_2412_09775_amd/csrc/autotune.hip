@@ -125,14 +125,17 @@ long loss_blocks(const Sampling& sm) {
 // ------------------------------------------------------------------ backward rows
 
 // ab: [v][2][Z][Y][X] (field 0 = a, 1 = b after the inverse Y pass, complex);
-// gam: [v][Z][2][Y][X] real (Gamma phase, absorption).  Replaces field 0 by the
-// inverse X transform of u_A = conj(Gamma b)/(N I_bg) and field 1 by that of
-// u_B = Gamma conj(a)/(N I_bg); dpart[v * wpp + wg] = sum Re(Gamma b conj(a)).
+// g: [v][Z][2][Y][Xh], the half spectra of dL/dH* after the inverse Y pass.  For
+// each row the kernel forms Gamma = Gamma_phase + i Gamma_abs in one inverse X
+// transform (the two real rows packed into one complex line), then replaces
+// field 0 by the inverse X transform of u_A = conj(Gamma b)/(N I_bg) and field 1
+// by that of u_B = Gamma conj(a)/(N I_bg); dpart[v * wpp + wg] =
+// sum Re(Gamma b conj(a)).
 template <int NS>
 __global__ __launch_bounds__(1024) void k_tf_rows_bwd(const double* __restrict__ partials,
                                                       long tiles_x, Sampling sm,
                                                       float2* __restrict__ ab,
-                                                      const float* __restrict__ gam,
+                                                      const float2* __restrict__ g,
                                                       double* __restrict__ dpart, int rows_per_wg,
                                                       long wg_per_patch, FftPlan plan) {
   extern __shared__ float2 smem[];
@@ -140,6 +143,7 @@ __global__ __launch_bounds__(1024) void k_tf_rows_bwd(const double* __restrict__
   __shared__ double ibg_s;
   const int Y = sm.ny, Z = sm.nz;
   const int X = NS > 0 ? NS : sm.nx;   // compile-time length for the index arithmetic
+  const int Xh = X / 2 + 1;
   float2* tw = smem;
   float2* buf = smem + X;
   const int tid = threadIdx.x, nthr = blockDim.x;
@@ -152,36 +156,46 @@ __global__ __launch_bounds__(1024) void k_tf_rows_bwd(const double* __restrict__
   const int z0 = (int)(row0 / Y), y0 = (int)(row0 - (long)z0 * Y);
   float2* a_src = ab + (v * 2 + 0) * rpp * X;
   float2* b_src = ab + (v * 2 + 1) * rpp * X;
+  const float2* g_src = g + v * rpp * 2 * Xh;
   if (tid == 0) {
     double t = 0.0;
     for (long i = 0; i < tiles_x; ++i) t += partials[v * tiles_x + i];
     ibg_s = t;
   }
   const int LS = row_stride(X);      // padded line pitch in LDS
-  auto slot = [&](int e) {           // line 2r: a (then u_A), line 2r + 1: b (then u_B)
+  // lines 2r, 2r + 1: a (then u_A), b (then u_B) of row r; line 2 nr + r: Gamma of row r
+  auto slot = [&](int e) {
     const int t = e / X;
     return t * LS + row_slot(e - t * X);
   };
-  gather_to_lds_map(buf, nr * 2 * X, tid, nthr, [&](int e) {
+  gather_to_lds_map(buf, nr * 3 * X, tid, nthr, [&](int e) {
     const int i = e % X;
     const int t = e / X;
-    const int f = t & 1, r = t >> 1;
-    const float2* src = f ? b_src : a_src;
-    return src[(row0 + r) * X + i];
+    if (t < 2 * nr) {
+      const int f = t & 1, r = t >> 1;
+      return (f ? b_src : a_src)[(row0 + r) * X + i];
+    }
+    // packed line of the two half spectra: Z_k = P_k + i A_k (Hermitian extension)
+    int y = y0 + (t - 2 * nr), z = z0;
+    while (y >= Y) { y -= Y; ++z; }
+    const float2* gp = g_src + ((long)(z * 2 + 0) * Y + y) * Xh;
+    const float2* ga = g_src + ((long)(z * 2 + 1) * Y + y) * Xh;
+    const bool mirror = 2 * i > X;
+    const int kk = mirror ? X - i : i;
+    float2 P = gp[kk], A = ga[kk];
+    if (kk == 0 || 2 * kk == X) { P.y = 0.f; A.y = 0.f; }   // Re of the inverse ignores them
+    if (mirror) { P.y = -P.y; A.y = -A.y; }
+    return make_float2(P.x - A.y, P.y + A.x);
   }, slot, [] {});
   __syncthreads();
-  fft_lines<NS, 0, false, kEmax, true>(buf, LdsLines{2 * nr, 1, LS, false, -1, true}, plan, tw, 1.f,
+  fft_lines<NS, 0, false, kEmax, true>(buf, LdsLines{3 * nr, 1, LS, false, -1, true}, plan, tw, 1.f,
                                        tid, nthr);
   const float k = (float)(1.0 / ((double)X * (double)Y * ibg_s));
   double dsum = 0.0;
   for (int e = tid; e < nr * X; e += nthr) {
     const int r = e / X, i = e - r * X;
     const int si = row_slot(i);
-    int y = y0 + r, z = z0;
-    while (y >= Y) { y -= Y; ++z; }
-    const float gph = gam[(((v * Z + z) * 2 + 0) * (long)Y + y) * X + i];
-    const float gab = gam[(((v * Z + z) * 2 + 1) * (long)Y + y) * X + i];
-    const float2 G = make_float2(gph, gab);
+    const float2 G = buf[(2 * nr + r) * LS + si];   // (Gamma_phase, Gamma_abs)
     const float2 a = buf[2 * r * LS + si], b = buf[(2 * r + 1) * LS + si];
     const float2 gb = cmul(G, b);
     dsum += (double)gb.x * a.x + (double)gb.y * a.y;     // Re(G b conj(a))
@@ -205,7 +219,7 @@ __global__ __launch_bounds__(1024) void k_tf_rows_bwd(const double* __restrict__
 int bwd_rows_per_wg(const Sampling& sm) {
   int R = 2048 / sm.nx;
   if (R < 1) R = 1;
-  while (R > 1 && 2L * R * sm.nx > kMaxElems) --R;
+  while (R > 1 && 3L * R * sm.nx > kMaxElems) --R;
   return R;
 }
 
@@ -215,19 +229,20 @@ long bwd_wg_per_patch(const Sampling& sm) {
 }
 
 hipError_t launch_tf_rows_bwd(const double* partials, const Sampling& sm, int nv, float2* ab,
-                              const float* gam, double* dpart, hipStream_t s) {
+                              const float2* g, double* dpart, hipStream_t s) {
+  if (3L * sm.nx > kMaxElems) return hipErrorInvalidValue;
   FftPlan plan;
   if (!make_plan(sm.nx, &plan)) return hipErrorInvalidValue;
   const int R = bwd_rows_per_wg(sm);
   const long wpp = bwd_wg_per_patch(sm);
   const long tiles_x = (sm.nx + tf_tile_width(sm) - 1) / tf_tile_width(sm);
-  const int thr = threads_for(2L * R * sm.nx);
-  const size_t lds = (size_t)(sm.nx + 2L * R * row_stride(sm.nx)) * sizeof(float2);
+  const int thr = threads_for(3L * R * sm.nx);
+  const size_t lds = (size_t)(sm.nx + 3L * R * row_stride(sm.nx)) * sizeof(float2);
   ScopedTiming _t("k_tf_rows_bwd", s);
 #define X_(NN)                                                                                   \
   case NN:                                                                                       \
     hipLaunchKernelGGL((k_tf_rows_bwd<NN>), dim3((unsigned)(wpp * nv)), dim3(thr), lds, s, partials, \
-                       tiles_x, sm, ab, gam, dpart, R, wpp, plan);                               \
+                       tiles_x, sm, ab, g, dpart, R, wpp, plan);                               \
     return hipGetLastError();
   switch (sm.nx) {
     WO_LATERAL_SIZES(X_)
@@ -236,7 +251,7 @@ hipError_t launch_tf_rows_bwd(const double* partials, const Sampling& sm, int nv
   }
 #undef X_
   hipLaunchKernelGGL((k_tf_rows_bwd<0>), dim3((unsigned)(wpp * nv)), dim3(thr), lds, s, partials,
-                     tiles_x, sm, ab, gam, dpart, R, wpp, plan);
+                     tiles_x, sm, ab, g, dpart, R, wpp, plan);
   return hipGetLastError();
 }
 

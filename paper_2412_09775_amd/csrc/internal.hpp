@@ -139,7 +139,7 @@ hipError_t launch_loss_grad(const DevOptics* opt, const TuneState* st, const Sam
                             const float2* D, float2* bank, double* lpart, int data_div,
                             hipStream_t s);
 hipError_t launch_tf_rows_bwd(const double* partials, const Sampling& sm, int nv, float2* ab,
-                              const float* gam, double* dpart, hipStream_t s);
+                              const float2* g, double* dpart, hipStream_t s);
 hipError_t launch_tf_grad_y(const DevOptics* opt, const Sampling& sm, int nv, const float2* ab,
                             double* gpart, double* ipart, hipStream_t s);
 hipError_t launch_adam(DevOptics* opt, TuneState* st, const Sampling& sm, int nv,
