@@ -345,15 +345,32 @@ __global__ __launch_bounds__(1024) void k_tf_grad_y(const DevOptics* __restrict_
   }
   double g[4] = {0.0, 0.0, 0.0, 0.0};
   const int zend = min(Z, (zc + 1) * ZC);
+  // the tile of plane z: element e = (ky, field, w) from ab; plane z + 1 is loaded
+  // into registers while plane z is transformed and contracted
+  const int ntile = Y * 2 * W;
+  auto load_plane = [&](int z, float2* t) {
+#pragma unroll
+    for (int i = 0; i < 2 * EPT; ++i) {
+      const int e = tid + i * nthr;
+      if (e < ntile) {
+        const int ky = e >> (wsh + 1);
+        const int r = e & (2 * W - 1);
+        const int f = r >> wsh, w = r & (W - 1);
+        const int kx = x0 + w;
+        t[i] = kx < X ? ab[(((v * 2 + f) * Z + z) * (long)Y + ky) * X + kx] : make_float2(0.f, 0.f);
+      }
+    }
+  };
+  float2 nxt[2 * EPT];
+  if (zc * ZC < zend) load_plane(zc * ZC, nxt);
   for (int z = zc * ZC; z < zend; ++z) {
-    gather_to_lds<2 * EPT>(buf, Y * 2 * W, tid, nthr, [&](int e) {
-      const int ky = e >> (wsh + 1);
-      const int r = e & (2 * W - 1);
-      const int f = r >> wsh, w = r & (W - 1);
-      const int kx = x0 + w;
-      return kx < X ? ab[(((v * 2 + f) * Z + z) * (long)Y + ky) * X + kx] : make_float2(0.f, 0.f);
-    });
+#pragma unroll
+    for (int i = 0; i < 2 * EPT; ++i) {
+      const int e = tid + i * nthr;
+      if (e < ntile) buf[e] = nxt[i];
+    }
     __syncthreads();
+    if (z + 1 < zend) load_plane(z + 1, nxt);
     fft_lines<NS, 0, true, 2 * EPT>(buf, LdsLines{2 * W, 2 * W, 1, true, pow2_shift(2 * W)}, plan, tw,
                                     1.f, tid, nthr);
     const double dzr = plane_z(z, sm) - o.defocus;
