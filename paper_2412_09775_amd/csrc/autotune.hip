@@ -216,8 +216,10 @@ __global__ __launch_bounds__(1024) void k_tf_rows_bwd(const double* __restrict__
   });
 }
 
+// Rows per workgroup of the backward row kernel (three LDS lines per row):
+// about 1024 elements per row group keeps several workgroups per CU.
 int bwd_rows_per_wg(const Sampling& sm) {
-  int R = 2048 / sm.nx;
+  int R = 1024 / sm.nx;
   if (R < 1) R = 1;
   while (R > 1 && 3L * R * sm.nx > kMaxElems) --R;
   return R;
