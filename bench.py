@@ -557,7 +557,8 @@ def restore_section(api, torch, dev, net, ntiles, cnn_iters, ms_iters, graph_mod
     res = {"workload": f"{ntiles} tiles, Z in {list(RESTORE_Z)}, Y and X in {list(RESTORE_YX)} "
                        f"({vox / 1e6:.1f} M voxels, {len(set(shapes))} distinct shapes), thin model, "
                        f"tuning defocus and zenith tilt, thin reconstruction of every tile; "
-                       f"use_graph={graph_mode}"}
+                       f"use_graph={graph_mode}; tiles_per_s from a repeated call with the same "
+                       f"buffers (graph reused), first_call_seconds includes the capture"}
 
     def run(label, M, iters, theta0, predict):
         ws = torch.empty(api.tune_workspace_size(nominal, M), dtype=torch.uint8, device=dev)
@@ -565,20 +566,25 @@ def restore_section(api, torch, dev, net, ntiles, cnn_iters, ms_iters, graph_mod
         small = [tile_optics((16, 128, 128))]
         api.restore_tiles(small, [tiles[0].new_zeros((16, 128, 128))], etas[:1], iters=1, lr=TUNE_LR,
                           lo=TUNE_LO, hi=TUNE_HI, multistart=M, mask=TUNE_MASK, use_graph=graph_mode)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        if predict:
-            pred = net.predict(learned_init.network_input(tiles))
-            theta0 = np.zeros((ntiles, 1, 4))
-            theta0[:, 0, :3] = np.clip(pred, np.array(TUNE_LO[:3]), np.array(TUNE_HI[:3]))
-        out, loss, _, _, f = api.restore_tiles(nominal, tiles, etas, iters=iters, lr=TUNE_LR, lo=TUNE_LO,
-                                               hi=TUNE_HI, multistart=M, theta0=theta0, nu_c=nucs,
-                                               mask=TUNE_MASK, use_graph=graph_mode, ws=ws, f_out=fo)
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
+        d = api.pack_stacks(tiles)
+        times = []
+        for _ in range(2):   # the second call reuses the graph the first one captured
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            if predict:
+                pred = net.predict(learned_init.network_input(tiles))
+                theta0 = np.zeros((ntiles, 1, 4))
+                theta0[:, 0, :3] = np.clip(pred, np.array(TUNE_LO[:3]), np.array(TUNE_HI[:3]))
+            out, loss, _, _, f = api.restore_tiles(nominal, d, etas, iters=iters, lr=TUNE_LR, lo=TUNE_LO,
+                                                   hi=TUNE_HI, multistart=M, theta0=theta0, nu_c=nucs,
+                                                   mask=TUNE_MASK, use_graph=graph_mode, ws=ws, f_out=fo)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+        dt = times[1]
         th = np.array([[o.defocus, o.na_det, o.tilt_zenith, o.tilt_azimuth] for o in out])
         med, per = norm_err(th, truth)
-        r = {"tiles_per_s": ntiles / dt, "voxels_per_s": vox / dt, "seconds": round(dt, 3), "starts": M,
+        r = {"tiles_per_s": ntiles / dt, "voxels_per_s": vox / dt, "seconds": round(dt, 3),
+             "first_call_seconds": round(times[0], 3), "starts": M,
              "tune_iters": iters, "median_norm_param_err": round(med, 4),
              "median_norm_err_defocus_na_tilt": per, "median_norm_err_defocus_tilt": tuned_err(th, truth)}
         if predict:

@@ -177,7 +177,11 @@ typedef struct wo_autotune_opts {
                               captured in a HIP graph and replayed `iters` times;
                               2: the whole call (iterations, final loss and, for
                               wo_restore_tiles, the reconstruction) captured in
-                              one HIP graph and launched once */
+                              one HIP graph and launched once.  The library keeps
+                              the graphs of its last 8 distinct calls and reuses
+                              one when a call repeats the shapes and samplings,
+                              the buffers (d, ws, f_out), the counts and the FFT
+                              schedule table; parameters may differ */
   int32_t tune_mask;       /* bit j set: theta_j is tuned */
   double lr[4];            /* Adam learning rates per parameter */
   double lo[4], hi[4];     /* box for theta (NA is further capped inside the shell) */

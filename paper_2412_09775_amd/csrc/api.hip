@@ -1,5 +1,6 @@
 // C ABI: validation, workspace layout and the launch sequence of each call.
 #include <math.h>
+#include <stdio.h>
 #include <string.h>
 
 #include <algorithm>
@@ -589,6 +590,39 @@ int capture_streams(CaptureStreams** out) {
   return WO_OK;
 }
 
+// Instantiated graphs of recent calls (a few; oldest evicted).  Used under
+// g_tune_mu.
+constexpr size_t kGraphCache = 8;
+std::vector<std::pair<std::string, hipGraphExec_t>> g_graphs;
+
+hipGraphExec_t graph_cache_find(const std::string& key) {
+  for (auto& kv : g_graphs)
+    if (kv.first == key) return kv.second;
+  return nullptr;
+}
+
+void graph_cache_insert(const std::string& key, hipGraphExec_t exec) {
+  if (g_graphs.size() >= kGraphCache) {
+    hipGraphExecDestroy(g_graphs.front().second);
+    g_graphs.erase(g_graphs.begin());
+  }
+  g_graphs.push_back({key, exec});
+}
+
+std::string graph_key(const wo_optics* o, int32_t n, const wo_autotune_opts* opts, int starts,
+                      int B, const void* ws, size_t ws_bytes, const float* d, const float* f_out) {
+  std::string k;
+  char b[256];
+  snprintf(b, sizeof(b), "%d %d %d %d %d %p %zu %p %p %llu|", n, opts->use_graph, opts->iters, starts,
+           B, ws, ws_bytes, (const void*)d, (const void*)f_out, fft_table_version());
+  k += b;
+  for (int i = 0; i < n; ++i) {
+    snprintf(b, sizeof(b), "%d %d %d %a %a %a;", o[i].nz, o[i].ny, o[i].nx, o[i].dz, o[i].dy, o[i].dx);
+    k += b;
+  }
+  return k;
+}
+
 // Longest-processing-time assignment of groups to branches: groups sorted by
 // work, each placed on the least loaded branch.
 std::vector<std::vector<int>> assign_branches(const std::vector<TuneGroup>& g, int B) {
@@ -661,47 +695,53 @@ int run_tune(wo_optics* o, int32_t n, const float* d, const double* eta,
     int B = opts->branches > 0 ? opts->branches : 4;
     if (B > (int)groups.size()) B = (int)groups.size();
     const std::vector<std::vector<int>> br = assign_branches(groups, B);
-    const bool was_timing = timing_enabled();
-    if (was_timing) wo_timing_enable(0);
     WO_TRY(hipEventRecord(cs->ready, hs));
     WO_TRY(hipStreamWaitEvent(cs->cap, cs->ready, 0));
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
-    hipError_t ce = hipStreamBeginCapture(cs->cap, hipStreamCaptureModeThreadLocal);
-    if (ce != hipSuccess) {
-      if (was_timing) wo_timing_enable(1);
-      return WO_EHIP;
-    }
-    int ist = WO_OK;
-    hipError_t fe = hipEventRecord(cs->fork, cs->cap);
-    for (int b = 0; b < B && fe == hipSuccess; ++b) fe = hipStreamWaitEvent(cs->br[b], cs->fork, 0);
-    for (int b = 0; b < B && fe == hipSuccess && !ist; ++b) {
-      for (int k : br[b]) {
-        if (opts->use_graph == 1) {
-          ist = tune_iteration(groups[k], w, starts, 1, cs->br[b]);
-        } else {
-          for (int it = 0; it < iters && !ist; ++it)
-            ist = tune_iteration(groups[k], w, starts, 1, cs->br[b]);
-          if (!ist) ist = tail(groups[k], cs->br[b]);
-        }
-        if (ist) break;
+    // A graph depends only on the shapes and samplings, the buffers, the counts
+    // and the FFT schedules (parameters live in the workspace): reuse it when a
+    // call repeats them.
+    const std::string key = graph_key(o, n, opts, starts, B, ws, ws_bytes, d, f_out);
+    hipGraphExec_t exec = graph_cache_find(key);
+    if (!exec) {
+      const bool was_timing = timing_enabled();
+      if (was_timing) wo_timing_enable(0);
+      hipGraph_t graph = nullptr;
+      hipError_t ce = hipStreamBeginCapture(cs->cap, hipStreamCaptureModeThreadLocal);
+      if (ce != hipSuccess) {
+        if (was_timing) wo_timing_enable(1);
+        return WO_EHIP;
       }
-    }
-    for (int b = 0; b < B && fe == hipSuccess; ++b) {
-      hipError_t e1 = hipEventRecord(cs->join[b], cs->br[b]);
-      hipError_t e2 = hipStreamWaitEvent(cs->cap, cs->join[b], 0);
-      if (e1 != hipSuccess) fe = e1;
-      else if (e2 != hipSuccess) fe = e2;
-    }
-    ce = hipStreamEndCapture(cs->cap, &graph);
-    if (was_timing) wo_timing_enable(1);
-    if (ist || fe != hipSuccess || ce != hipSuccess) {
-      if (graph) hipGraphDestroy(graph);
-      return ist ? ist : WO_EHIP;
-    }
-    if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+      int ist = WO_OK;
+      hipError_t fe = hipEventRecord(cs->fork, cs->cap);
+      for (int b = 0; b < B && fe == hipSuccess; ++b) fe = hipStreamWaitEvent(cs->br[b], cs->fork, 0);
+      for (int b = 0; b < B && fe == hipSuccess && !ist; ++b) {
+        for (int k : br[b]) {
+          if (opts->use_graph == 1) {
+            ist = tune_iteration(groups[k], w, starts, 1, cs->br[b]);
+          } else {
+            for (int it = 0; it < iters && !ist; ++it)
+              ist = tune_iteration(groups[k], w, starts, 1, cs->br[b]);
+            if (!ist) ist = tail(groups[k], cs->br[b]);
+          }
+          if (ist) break;
+        }
+      }
+      for (int b = 0; b < B && fe == hipSuccess; ++b) {
+        hipError_t e1 = hipEventRecord(cs->join[b], cs->br[b]);
+        hipError_t e2 = hipStreamWaitEvent(cs->cap, cs->join[b], 0);
+        if (e1 != hipSuccess) fe = e1;
+        else if (e2 != hipSuccess) fe = e2;
+      }
+      ce = hipStreamEndCapture(cs->cap, &graph);
+      if (was_timing) wo_timing_enable(1);
+      if (ist || fe != hipSuccess || ce != hipSuccess) {
+        if (graph) hipGraphDestroy(graph);
+        return ist ? ist : WO_EHIP;
+      }
+      const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
       hipGraphDestroy(graph);
-      return WO_EHIP;
+      if (ie != hipSuccess) return WO_EHIP;
+      graph_cache_insert(key, exec);
     }
     const int launches = opts->use_graph == 1 ? iters : 1;
     hipError_t le = hipSuccess;
@@ -709,8 +749,6 @@ int run_tune(wo_optics* o, int32_t n, const float* d, const double* eta,
     hipError_t re = hipEventRecord(cs->done, cs->cap);
     if (re == hipSuccess) re = hipStreamWaitEvent(hs, cs->done, 0);
     hipError_t se = hipStreamSynchronize(cs->cap);
-    hipGraphExecDestroy(exec);
-    hipGraphDestroy(graph);
     if (le != hipSuccess || re != hipSuccess || se != hipSuccess) return WO_EHIP;
     if (opts->use_graph == 1)
       for (auto& g : groups) {

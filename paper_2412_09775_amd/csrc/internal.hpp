@@ -72,6 +72,8 @@ struct FftChoice {
 // Table entry for k, if any.
 bool fft_lookup(const FftKey& k, FftChoice* c);
 void fft_store(const FftKey& k, const FftChoice& c);
+// Changes whenever the table changes (graphs captured before are stale).
+unsigned long long fft_table_version();
 // Every schedule the launcher of k accepts (the first is the default).
 std::vector<FftChoice> fft_candidates(const FftKey& k);
 // While a tuning run records, each tunable launch registers its key and a

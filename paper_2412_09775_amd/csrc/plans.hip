@@ -21,6 +21,7 @@ namespace wo {
 namespace {
 std::mutex g_plan_mu;
 std::map<FftKey, FftChoice> g_plans;
+unsigned long long g_plan_version = 0;
 thread_local std::vector<std::pair<FftKey, std::function<hipError_t()>>>* g_rec = nullptr;
 
 const char* kind_name(int k) {
@@ -89,6 +90,12 @@ bool fft_lookup(const FftKey& k, FftChoice* c) {
 void fft_store(const FftKey& k, const FftChoice& c) {
   std::lock_guard<std::mutex> lk(g_plan_mu);
   g_plans[k] = c;
+  ++g_plan_version;
+}
+
+unsigned long long fft_table_version() {
+  std::lock_guard<std::mutex> lk(g_plan_mu);
+  return g_plan_version;
 }
 
 bool fft_recording() { return g_rec != nullptr; }
@@ -196,6 +203,7 @@ int wo_fft_plans_import(const char* text) {
 int wo_fft_plans_clear(void) {
   std::lock_guard<std::mutex> lk(g_plan_mu);
   g_plans.clear();
+  ++g_plan_version;
   return WO_OK;
 }
 

@@ -137,3 +137,26 @@ def test_graph_modes_equal_plain_launches(gpu_lib, tiles, mode, branches):
     assert np.array_equal(a[2], b[2]) and np.array_equal(a[3], b[3])
     for x, y in zip(a[4], b[4]):
         assert np.array_equal(x.cpu().numpy(), y.cpu().numpy())
+
+
+@pytest.mark.parametrize("mode", [1, 2])
+def test_reused_graph_takes_new_parameters(gpu_lib, tiles, mode):
+    """A repeated call with the same buffers reuses its graph; the new starting
+    parameters still take effect (they live in the workspace, not in the graph)."""
+    import torch
+    starts, stacks, etas, nucs = tiles
+    print(f"[case] graph reuse mode {mode}", flush=True)
+    d = gpu_lib.pack_stacks(dev(stacks))
+    ws = torch.empty(gpu_lib.tune_workspace_size(starts, 1), dtype=torch.uint8, device="cuda")
+    fo = torch.empty(sum(2 * o.ny * o.nx for o in starts), dtype=torch.float32, device="cuda")
+    kw = dict(iters=3, nu_c=nucs, lr=LR, lo=LO, hi=HI, ws=ws, f_out=fo)
+    th_a = np.stack([[at.theta_of(o)] for o in starts])
+    th_b = th_a + np.array([0.25, 0.0, 0.05, 0.0])
+    gpu_lib.restore_tiles(starts, d, etas, use_graph=mode, theta0=th_a, **kw)
+    b1 = gpu_lib.restore_tiles(starts, d, etas, use_graph=mode, theta0=th_b, **kw)
+    f1 = [x.cpu().numpy() for x in b1[4]]
+    ref = gpu_lib.restore_tiles(starts, d, etas, use_graph=0, theta0=th_b, iters=3, nu_c=nucs, lr=LR,
+                                lo=LO, hi=HI)
+    assert np.array_equal(b1[2], ref[2]) and np.array_equal(b1[1], ref[1])
+    for x, y in zip(f1, ref[4]):
+        assert np.array_equal(x, y.cpu().numpy())
