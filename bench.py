@@ -191,7 +191,8 @@ def main():
     ap.add_argument("--no-fft-tune", action="store_true", help="keep the default FFT schedules")
     ap.add_argument("--fft-plans", default="", help="import an FFT schedule table instead of tuning")
     ap.add_argument("--save-fft-plans", default="", help="write the FFT schedule table used")
-    ap.add_argument("--restore-graph", type=int, default=1, choices=(0, 1, 2))
+    ap.add_argument("--restore-graph", type=int, default=2, choices=(0, 1, 2),
+                    help="graph mode of the CNN-started restoration (multistart uses 1)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for HBM counters)")
     ap.add_argument("--summarise-trace", default="", help="(no GPU) write the kernel-duration "
@@ -557,15 +558,16 @@ def restore_section(api, torch, dev, net, ntiles, cnn_iters, ms_iters, graph_mod
     res = {"workload": f"{ntiles} tiles, Z in {list(RESTORE_Z)}, Y and X in {list(RESTORE_YX)} "
                        f"({vox / 1e6:.1f} M voxels, {len(set(shapes))} distinct shapes), thin model, "
                        f"tuning defocus and zenith tilt, thin reconstruction of every tile; "
-                       f"use_graph={graph_mode}; tiles_per_s from a repeated call with the same "
-                       f"buffers (graph reused), first_call_seconds includes the capture"}
+                       f"tiles_per_s from a repeated call with the same buffers (graph reused), "
+                       f"first_call_seconds includes the capture"}
 
-    def run(label, M, iters, theta0, predict):
+    def run(label, M, iters, theta0, predict, graph_mode, branches):
         ws = torch.empty(api.tune_workspace_size(nominal, M), dtype=torch.uint8, device=dev)
         fo = torch.empty(sum(2 * y * x for _, y, x in shapes), dtype=torch.float32, device=dev)
         small = [tile_optics((16, 128, 128))]
         api.restore_tiles(small, [tiles[0].new_zeros((16, 128, 128))], etas[:1], iters=1, lr=TUNE_LR,
-                          lo=TUNE_LO, hi=TUNE_HI, multistart=M, mask=TUNE_MASK, use_graph=graph_mode)
+                          lo=TUNE_LO, hi=TUNE_HI, multistart=M, mask=TUNE_MASK, use_graph=graph_mode,
+                          branches=branches)
         d = api.pack_stacks(tiles)
         times = []
         for _ in range(2):   # the second call reuses the graph the first one captured
@@ -577,14 +579,16 @@ def restore_section(api, torch, dev, net, ntiles, cnn_iters, ms_iters, graph_mod
                 theta0[:, 0, :3] = np.clip(pred, np.array(TUNE_LO[:3]), np.array(TUNE_HI[:3]))
             out, loss, _, _, f = api.restore_tiles(nominal, d, etas, iters=iters, lr=TUNE_LR, lo=TUNE_LO,
                                                    hi=TUNE_HI, multistart=M, theta0=theta0, nu_c=nucs,
-                                                   mask=TUNE_MASK, use_graph=graph_mode, ws=ws, f_out=fo)
+                                                   mask=TUNE_MASK, use_graph=graph_mode,
+                                                   branches=branches, ws=ws, f_out=fo)
             torch.cuda.synchronize()
             times.append(time.perf_counter() - t0)
         dt = times[1]
         th = np.array([[o.defocus, o.na_det, o.tilt_zenith, o.tilt_azimuth] for o in out])
         med, per = norm_err(th, truth)
         r = {"tiles_per_s": ntiles / dt, "voxels_per_s": vox / dt, "seconds": round(dt, 3),
-             "first_call_seconds": round(times[0], 3), "starts": M,
+             "first_call_seconds": round(times[0], 3), "use_graph": graph_mode, "branches": branches,
+             "starts": M,
              "tune_iters": iters, "median_norm_param_err": round(med, 4),
              "median_norm_err_defocus_na_tilt": per, "median_norm_err_defocus_tilt": tuned_err(th, truth)}
         if predict:
@@ -594,9 +598,13 @@ def restore_section(api, torch, dev, net, ntiles, cnn_iters, ms_iters, graph_mod
         del ws, fo
         return r
 
-    res["multistart_8"] = run("multistart_8", 8, ms_iters, grid_starts(ntiles, TUNE["na_det"]), False)
+    # graph modes: the whole call as one launch (use_graph 2) suits the short CNN-started
+    # tune; the 100-iteration multistart replays a one-iteration graph (use_graph 1),
+    # whose capture is 100 times smaller
+    res["multistart_8"] = run("multistart_8", 8, ms_iters, grid_starts(ntiles, TUNE["na_det"]), False,
+                              1, 4)
     if net is not None:
-        res["cnn_init"] = run("cnn_init", 1, cnn_iters, None, True)
+        res["cnn_init"] = run("cnn_init", 1, cnn_iters, None, True, graph_mode, 8)
         res["cnn_init"]["speedup_vs_multistart_8"] = round(
             res["cnn_init"]["tiles_per_s"] / res["multistart_8"]["tiles_per_s"], 2)
     return res
