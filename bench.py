@@ -359,6 +359,8 @@ def main():
                                            args.cnn_tune_iters)
         if train:
             out["autotune"]["cnn_training"] = train
+        if not args.no_cpu_baseline:
+            out["autotune"]["cpu_baseline"] = cpu_baseline_autotune()
         if args.restore_tiles > 0:
             out["restore"] = restore_section(api, torch, dev, net, args.restore_tiles, args.cnn_tune_iters,
                                              args.tune_iters, args.restore_graph)
@@ -608,6 +610,37 @@ def restore_section(api, torch, dev, net, ntiles, cnn_iters, ms_iters, graph_mod
         res["cnn_init"]["speedup_vs_multistart_8"] = round(
             res["cnn_init"]["tiles_per_s"] / res["multistart_8"]["tiles_per_s"], 2)
     return res
+
+
+def cpu_baseline_autotune(iters_timed=20, iters_full=100):
+    """FP64 oracle auto-tune (analytic gradient + Adam) of one 32x128x128 patch for a
+    bounded number of iterations on all host cores, extrapolated to the full count."""
+    import scipy.fft as sfft
+
+    import synth
+    from oracle import autotune as at
+    from oracle import linear
+    from oracle import optics as op
+    from oracle import tf as tfm
+
+    cores = len(os.sched_getaffinity(0))
+    o = op.Optics(model=op.LABELFREE_THIN, nz=TUNE["nz"], ny=TUNE["ny"], nx=TUNE["nx"], dz=TUNE["dz"],
+                  dy=TUNE["dy"], dx=TUNE["dx"], wavelength=TUNE["wavelength"], na_ill=TUNE["na_ill"],
+                  na_det=TUNE["na_det"], n_medium=TUNE["n_medium"], edge_width=TUNE["edge_width"])
+    truth = o.replace(defocus=0.7, tilt_zenith=0.2)
+    f = synth.thin_cells((o.ny, o.nx), o.dx, 20, seed=4101)
+    d = linear.forward(tfm.labelfree_thin(truth), f) + synth.gaussian_noise((o.nz, o.ny, o.nx), 0.03, 4102)
+    eta = 1e-2 * linear.max_singular_value_sq(tfm.labelfree_thin(o))
+    start = o.replace(tilt_zenith=math.radians(15.0))
+    t0 = time.perf_counter()
+    with sfft.set_workers(cores):
+        at.autotune(start, d, eta, at.nominal_cutoff(o), iters_timed, np.array(TUNE_LR),
+                    np.array(TUNE_LO), np.array(TUNE_HI), mask=tuple((TUNE_MASK >> j) & 1 for j in range(4)))
+    dt = time.perf_counter() - t0
+    per_patch = dt * iters_full / iters_timed
+    return {"value": 1.0 / per_patch, "unit": "patches/s", "cores": cores, "kind": "oracle",
+            "sample": f"1 patch 32x128x128, {iters_timed} Adam iterations (FP64 analytic gradient) in "
+                      f"{dt:.1f} s, extrapolated to {iters_full} iterations"}
 
 
 def cpu_baseline(o, nz):
