@@ -21,6 +21,10 @@ against the paper:
 * ``autotune`` -- mid-band power loss, Adam, finite-difference and analytic
                   parameter gradients (Methods, "Cell-scale optical pooled
                   screen data").
+* ``stitch``   -- tiling of a field of view and EDT-weighted blending of the
+                  restored tiles (Methods, OPS tiling and stitching).
+* ``cnn``      -- the parameter-regression network of the learned initialiser
+                  (not in the paper).
 
 Conventions the paper leaves open are fixed once here and listed as
 "readings" in the design notes; each function names the reading it uses.
@@ -33,4 +37,4 @@ value printed in the paper (parity unpinned; judged against synthetic ground
 truth only).
 """
 
-from . import optics, tf, linear, autotune, cnn  # noqa: F401
+from . import optics, tf, linear, autotune, cnn, stitch  # noqa: F401
