@@ -215,6 +215,31 @@ int wo_restore_tiles(wo_optics* o, int32_t n, const float* d, const double* eta,
                      const wo_autotune_opts* opts, double* loss_out, float* f_out, void* ws,
                      size_t ws_bytes, void* stream);
 
+/* ---------------------------------------------------------------- field of view
+ * Shift-variant restoration of a large field of view tiles it, restores every
+ * tile with its own parameters (wo_restore_tiles) and blends the tiles back
+ * (Methods, "Cell-scale optical pooled screen data": a grid of tiles with 20 %
+ * overlap; "Organelle-scale optical pooled screen data": a 5 x 5 grid with 25
+ * pixels of overlap, stitched with linearly weighted Euclidean-distance-
+ * transform blending). */
+
+/* Tile size and starts along one axis of `length` pixels: `count` (1..32)
+ * evenly spaced tiles, the first at 0 and the last flush with the far edge
+ * (one tile: centred), of the smallest even {2,3,5}-smooth size that gives at
+ * least `overlap` pixels between neighbours.  tile: host int32; starts: host
+ * int32[count].  WO_EINVAL if the tiles would not fit. */
+int wo_tile_grid(int32_t length, int32_t count, int32_t overlap, int32_t* tile, int32_t* starts);
+
+/* Blends tiles into a field: out[p][y][x] = sum_t w_t f_t[p][y - y0_t][x - x0_t]
+ * / sum_t w_t over the tiles t covering (y, x), with w_t the tile's distance
+ * transform min(u + 1, ty - u, v + 1, tx - v) at tile pixel (u, v) (0 where no
+ * tile covers).  tiles: device [ny_t * nx_t][P][ty][tx], row-major over the
+ * grid; ys, xs: host int32 starts (ascending, inside the field; grid up to
+ * 32 x 32); out: device [P][H][W]. */
+int wo_stitch_tiles(const float* tiles, int32_t ny_t, int32_t nx_t, int32_t P, int32_t ty, int32_t tx,
+                    const int32_t* ys, const int32_t* xs, int32_t H, int32_t W, float* out,
+                    void* stream);
+
 /* ---------------------------------------------------------------- FFT schedule tuner
  * Not in the paper (its transforms are library calls).  Every FFT pass of the
  * library -- rows along X (real <-> half spectrum), strided columns along Y

@@ -36,7 +36,8 @@ SYMBOLS = ("wo_bank_shape", "wo_workspace_size", "wo_transfer_function", "wo_for
            "wo_cnn_param_count", "wo_cnn_workspace_size", "wo_cnn_forward", "wo_cnn_gradient",
            "wo_cnn_train_step", "wo_conv3d_forward", "wo_conv3d_input_grad", "wo_conv3d_weight_grad",
            "wo_synth_thin_cells", "wo_add_gaussian_noise", "wo_crop_stacks", "wo_fft_tune",
-           "wo_fft_plans_export", "wo_fft_plans_import", "wo_fft_plans_clear", "wo_fft_candidates")
+           "wo_fft_plans_export", "wo_fft_plans_import", "wo_fft_plans_clear", "wo_fft_candidates",
+           "wo_tile_grid", "wo_stitch_tiles")
 
 _FIELDS = ("model", "nz", "ny", "nx", "dz", "dy", "dx", "wavelength", "na_ill", "na_det",
            "n_medium", "defocus", "tilt_zenith", "tilt_azimuth", "edge_width", "swing")
@@ -130,6 +131,9 @@ def load(path: str = LIB_PATH):
     lib.wo_conv3d_weight_grad.argtypes = conv + [vp, sz, vp]
     lib.wo_synth_thin_cells.argtypes = [vp, i32, i32, i32, f64, i32, u64, vp]
     lib.wo_add_gaussian_noise.argtypes = [vp, i64, f64, u64, vp]
+    i32p = ctypes.POINTER(i32)
+    lib.wo_tile_grid.argtypes = [i32, i32, i32, i32p, i32p]
+    lib.wo_stitch_tiles.argtypes = [vp, i32, i32, i32, i32, i32, i32p, i32p, i32, i32, vp, vp]
     szp = ctypes.POINTER(ctypes.c_size_t)
     lib.wo_fft_tune.argtypes = [i32, op, i32, vp, vp, vp, f64, i32, vp, sz, vp]
     lib.wo_fft_plans_export.argtypes = [ctypes.c_char_p, sz, szp]
@@ -611,3 +615,28 @@ def fft_plans_clear():
 def fft_candidates(key_line: str) -> list:
     """Schedules (export-format lines) the pass "kind n m batch extra" accepts."""
     return [ln for ln in _text_call(load().wo_fft_candidates, key_line.encode()).splitlines() if ln]
+
+
+# ---------------------------------------------------------------- field of view
+
+def tile_grid(length: int, count: int, overlap: int):
+    """(tile size, starts) along one axis (see ``wo_tile_grid``)."""
+    T = ctypes.c_int32(0)
+    starts = (ctypes.c_int32 * count)()
+    _check(load().wo_tile_grid(int(length), int(count), int(overlap), ctypes.byref(T), starts),
+           "wo_tile_grid")
+    return T.value, list(starts)
+
+
+def stitch_tiles(tiles, ys, xs, H, W, out=None, stream=None):
+    """Blend tiles (n_y * n_x, P, T_y, T_x) into a (P, H, W) field (see ``wo_stitch_tiles``)."""
+    import torch
+    tiles = tiles.contiguous()
+    n, P, ty, tx = tiles.shape
+    if out is None:
+        out = torch.empty((P, H, W), dtype=torch.float32, device=tiles.device)
+    ya = (ctypes.c_int32 * len(ys))(*ys)
+    xa = (ctypes.c_int32 * len(xs))(*xs)
+    _check(load().wo_stitch_tiles(_ptr(tiles), len(ys), len(xs), P, ty, tx, ya, xa, int(H), int(W),
+                                  _ptr(out), _stream(stream)), "wo_stitch_tiles")
+    return out

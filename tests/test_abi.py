@@ -120,3 +120,11 @@ def test_fft_schedule_table_host_logic(lib):
     assert api.fft_plans_export() == pick + "\n"   # a rejected import changes nothing
     api.fft_plans_clear()
     assert api.fft_plans_export() == ""
+
+
+def test_tile_grid_host_logic_matches_the_oracle(lib):
+    from oracle import stitch
+    for args in [(2048, 6, 410), (1000, 5, 25), (300, 1, 0), (130, 2, 0), (2048, 6, 82), (120, 2, 20)]:
+        assert api.tile_grid(*args) == stitch.tile_grid(*args)
+    with pytest.raises(api.WoError):
+        api.tile_grid(100, 2, 200)          # tiles would not fit
