@@ -188,6 +188,7 @@ def main():
     ap.add_argument("--cnn-epochs", type=int, default=8)
     ap.add_argument("--cnn-tune-iters", type=int, default=20)
     ap.add_argument("--restore-tiles", type=int, default=64)
+    ap.add_argument("--fov-size", type=int, default=2048, help="field of view side (0: skip)")
     ap.add_argument("--no-fft-tune", action="store_true", help="keep the default FFT schedules")
     ap.add_argument("--fft-plans", default="", help="import an FFT schedule table instead of tuning")
     ap.add_argument("--save-fft-plans", default="", help="write the FFT schedule table used")
@@ -359,6 +360,8 @@ def main():
                                            args.cnn_tune_iters)
         if train:
             out["autotune"]["cnn_training"] = train
+        if net is not None and args.fov_size > 0:
+            out["fov"] = fov_section(api, torch, dev, net, args.cnn_tune_iters, size=args.fov_size)
         if not args.no_cpu_baseline:
             out["autotune"]["cpu_baseline"] = cpu_baseline_autotune()
         if args.restore_tiles > 0:
@@ -610,6 +613,61 @@ def restore_section(api, torch, dev, net, ntiles, cnn_iters, ms_iters, graph_mod
         res["cnn_init"]["speedup_vs_multistart_8"] = round(
             res["cnn_init"]["tiles_per_s"] / res["multistart_8"]["tiles_per_s"], 2)
     return res
+
+
+def fov_section(api, torch, dev, net, cnn_iters, size=2048, nz=32, grid=6, overlap_frac=0.2):
+    """Shift-variant restoration of one field of view: a grid x grid of tiles with
+    about 20 % overlap (Methods, OPS data), each tile CNN-started, auto-tuned
+    (defocus, tilt) and reconstructed in one call, then blended with EDT weights.
+    Synthetic data: cells over the whole field; each tile imaged with its own
+    parameters (defocus drifting across the field, tilt growing towards the
+    periphery), and the tile images blended with the same weights."""
+    from paper_2412_09775_amd import fov
+    T0 = api.tile_grid(size, grid, 0)[0]
+    T, starts = api.tile_grid(size, grid, int(round(overlap_frac * T0)))
+    n = grid * grid
+    cy = np.array([s + T / 2 for s in starts]) - size / 2
+    truth = np.zeros((n, 3))
+    for iy in range(grid):
+        for ix in range(grid):
+            r = math.hypot(cy[iy], cy[ix]) / (size / math.sqrt(2))
+            truth[iy * grid + ix] = [-1.5 + 3.0 * ix / (grid - 1), 1.15 + 0.1 * (iy / (grid - 1) - 0.5),
+                                     math.radians(25.0) * r]
+    ew = 0.5 * T / 128.0
+    tmpl = api.Optics(**dict(TUNE, nz=nz, ny=T, nx=T, edge_width=ew))
+    cells = api.synth_thin_cells(1, size, size, TUNE["dx"], round(20 * size * size / 128 ** 2), 9001, dev)
+    obj_tiles = torch.stack([cells[0, :, y:y + T, x:x + T] for y in starts for x in starts]).contiguous()
+    opts_true = [api.Optics(**dict(TUNE, nz=nz, ny=T, nx=T, edge_width=ew, defocus=t[0], na_det=t[1],
+                                   tilt_zenith=t[2])) for t in truth]
+    imgs = torch.empty((n, nz, T, T), dtype=torch.float32, device=dev)
+    for i in range(n):
+        imgs[i] = api.forward([opts_true[i]], api.transfer_function([opts_true[i]], device=dev),
+                              obj_tiles[i:i + 1])[0]
+    stack = torch.stack([api.stitch_tiles(imgs[:, z:z + 1], starts, starts, size, size)[0]
+                         for z in range(nz)])
+    api.add_gaussian_noise(stack, 0.0317, 9002)
+    del imgs, obj_tiles, cells
+    eta = 1e-2 * thin_sigma_max_sq(api.transfer_function([tmpl], device=dev))
+    nu_c = (TUNE["na_det"] + TUNE["na_ill"]) / TUNE["wavelength"]
+    kw = dict(grid=(grid, grid), overlap=(int(round(overlap_frac * T0)),) * 2, eta=eta, net=net,
+              iters=cnn_iters, mask=TUNE_MASK, lr=TUNE_LR, lo=TUNE_LO, hi=TUNE_HI, nu_c=nu_c)
+    fov.restore_fov(stack, tmpl, **kw)            # capture
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    field, out, loss, geom = fov.restore_fov(stack, tmpl, **kw)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    th = np.array([[o.defocus, o.na_det, o.tilt_zenith, o.tilt_azimuth] for o in out])
+    med, per = norm_err(th, truth)
+    vox = nz * size * size
+    print(f"[bench] fov {size}x{size}: {dt * 1e3:.0f} ms, median err {med:.3f}", file=sys.stderr,
+          flush=True)
+    return {"workload": f"field of view {nz}x{size}x{size}, {grid}x{grid} tiles of {T}x{T} "
+                        f"(overlap >= {int(round(overlap_frac * T0))} px), CNN start + {cnn_iters} "
+                        f"iterations per tile, EDT-weighted stitching",
+            "fov_per_s": 1.0 / dt, "voxels_per_s": vox / dt, "seconds": round(dt, 3),
+            "median_norm_param_err": round(med, 4), "median_norm_err_defocus_na_tilt": per,
+            "median_norm_err_defocus_tilt": tuned_err(th, truth)}
 
 
 def cpu_baseline_autotune(iters_timed=20, iters_full=100):
