@@ -38,6 +38,7 @@ FLUOR_3D = 0
 LABELFREE_3D = 1
 LABELFREE_THIN = 2
 POL5_3D = 3
+SECTORS9_3D = 4
 
 
 @dataclasses.dataclass
@@ -134,6 +135,36 @@ def illumination_pupil(o: Optics) -> np.ndarray:
     fy, fx = lateral_frequencies(o)
     cy, cx = source_centre(o)
     return radius_disc(fy, fx, o.na_ill / o.wavelength, o.edge_width * o.dnu, cy, cx)
+
+
+def octant(dy, dx):
+    """Sector index k of the direction (dy, dx): its azimuth lies in [k pi/4, (k+1) pi/4)
+    measured from +x towards +y; the origin is in sector 0 (reading R17).  Written
+    with comparisons only, so equal inputs give equal decisions on any machine."""
+    dy = np.asarray(dy, dtype=np.float64)
+    dx = np.asarray(dx, dtype=np.float64)
+    k = np.full(np.broadcast(dy, dx).shape, 6, dtype=np.int64)
+    q0 = (dy >= 0) & (dx > 0)
+    q1 = (dx <= 0) & (dy > 0)
+    q2 = (dy <= 0) & (dx < 0)
+    q3 = ~(q0 | q1 | q2)                      # dy < 0, dx >= 0, or the origin
+    k = np.where(q0, np.where(dy < dx, 0, 1), k)
+    k = np.where(q1, np.where(dy > -dx, 2, 3), k)
+    k = np.where(q2, np.where(dy > dx, 4, 5), k)
+    k = np.where(q3, np.where(dx < -dy, 6, 7), k)
+    return np.where((dy == 0) & (dx == 0), 0, k)
+
+
+def sector_pupil(o: Optics, c: int) -> np.ndarray:
+    """Illumination pupil of aperture c of the 9-aperture scheme (Results, cardiomyocytes;
+    Methods "Cardiomyocyte reconstructions"): sectors c = 0..7 of the source disc,
+    split by azimuth about its centre q0, and the full disc for c = 8 (reading R17)."""
+    S = illumination_pupil(o)
+    if c == 8:
+        return S
+    fy, fx = lateral_frequencies(o)
+    cy, cx = source_centre(o)
+    return S * (octant(fy - cy, fx - cx) == c)
 
 
 def axial_wavenumber(o: Optics, wavelength: float | None = None) -> np.ndarray:

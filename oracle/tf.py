@@ -36,12 +36,14 @@ def _planes(o: op.Optics) -> np.ndarray:
     return op.z_planes_thin(o) if o.model == op.LABELFREE_THIN else op.z_planes_3d(o)
 
 
-def labelfree_point_response(o: op.Optics) -> np.ndarray:
-    """c_z(x) for every plane: (Z, Y, X) complex (Table 1 scalar label-free row).
+def labelfree_point_response(o: op.Optics, S: np.ndarray | None = None) -> np.ndarray:
+    """c_z(x) for every plane: (Z, Y, X) complex (Table 1 scalar label-free row),
+    for the illumination pupil S (default: the optics' disc).
 
     The phase PSF is 2 Re c and the absorption PSF is -2 Im c.
     """
-    S = op.illumination_pupil(o)
+    if S is None:
+        S = op.illumination_pupil(o)
     P = op.detection_pupil(o)
     g = op.greens_spectrum(o)
     ibg = float(np.sum(S * P * P))
@@ -153,6 +155,17 @@ def pol5_3d(o: op.Optics) -> np.ndarray:
     return k.real[:, :, None, None, None] * hp + k.imag[:, :, None, None, None] * ha
 
 
+def sectors9_3d(o: op.Optics) -> np.ndarray:
+    """(9, 1, Z, Y, X) phase bank of the 9-aperture scheme: channel c is the 3D phase
+    TF of the label-free model under aperture c (8 sectors, then the full disc),
+    each normalised by its own background sum_q S_c P^2 (Fig. 4c: a 9 x 1 column)."""
+    out = np.empty((9, 1, o.nz, o.ny, o.nx), dtype=np.complex128)
+    for c in range(9):
+        cz = labelfree_point_response(o, op.sector_pupil(o, c))
+        out[c, 0] = sfft.fftn(2.0 * cz.real)
+    return out
+
+
 def transfer_function(o: op.Optics) -> np.ndarray:
     """TF bank of the model: (C, P, Z, Y, X) for 3D models, (C=Z, P=2, Y, X) for thin."""
     op.check_optics(o)
@@ -164,6 +177,8 @@ def transfer_function(o: op.Optics) -> np.ndarray:
         return labelfree_thin(o)
     if o.model == op.POL5_3D:
         return pol5_3d(o)
+    if o.model == op.SECTORS9_3D:
+        return sectors9_3d(o)
     raise ValueError(f"unknown model {o.model}")
 
 
@@ -177,6 +192,8 @@ def bank_shape(o: op.Optics):
         return o.nz, 2, 2
     if o.model == op.POL5_3D:
         return 5, 4, 3
+    if o.model == op.SECTORS9_3D:
+        return 9, 1, 3
     raise ValueError(o.model)
 
 

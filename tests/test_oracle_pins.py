@@ -218,9 +218,10 @@ def test_fluorescence_infocus_otf_is_close_to_airy():
 
 # ---------------------------------------------------------------- label-free TFs
 
-def abbe_point_response(o):
+def abbe_point_response(o, S=None):
     """Brute-force 'summing over the source': c(x, z) from the double sum over q and p."""
-    S = op.illumination_pupil(o)
+    if S is None:
+        S = op.illumination_pupil(o)
     P = op.detection_pupil(o)
     fy, fx = op.lateral_frequencies(o)
     kz = op.axial_wavenumber(o)
@@ -397,3 +398,49 @@ def test_direct_frequency_sum_equals_the_bank():
     for kz, ky, kx in [(0, 0, 0), (1, 2, 3), (7, 31, 5), (3, 10, 30), (4, 16, 16)]:
         a, b = tfm.labelfree_3d_at(o, kz, ky, kx)
         assert abs(a - hp[kz, ky, kx]) < 1e-12 and abs(b - ha[kz, ky, kx]) < 1e-12
+
+
+# ---------------------------------------------------------------- 9-aperture bank
+
+def test_octant_is_the_azimuth_sector():
+    rng = np.random.default_rng(5)
+    dy, dx = rng.standard_normal((2, 2000))
+    ang = np.mod(np.arctan2(dy, dx), 2 * np.pi)
+    assert np.array_equal(op.octant(dy, dx), np.floor(ang / (np.pi / 4)).astype(int))
+    # boundaries belong to the sector they open; the origin to sector 0
+    pts = [(0, 1, 0), (1, 1, 1), (1, 0, 2), (1, -1, 3), (0, -1, 4), (-1, -1, 5), (-1, 0, 6), (-1, 1, 7),
+           (0, 0, 0)]
+    for y, x, k in pts:
+        assert int(op.octant(float(y), float(x))) == k
+
+
+def test_sectors_partition_the_source_and_their_tfs_add_up():
+    o = lf_optics(model=op.SECTORS9_3D, nz=8, ny=32, nx=32, tilt_zenith=0.15, tilt_azimuth=0.4)
+    S = op.illumination_pupil(o)
+    parts = [op.sector_pupil(o, c) for c in range(8)]
+    assert np.array_equal(np.sum(parts, axis=0), S) and np.array_equal(op.sector_pupil(o, 8), S)
+    P = op.detection_pupil(o)
+    bank = tfm.sectors9_3d(o)
+    ib = [np.sum(Sc * P * P) for Sc in parts]
+    # the unnormalised responses are linear in S: sum_c I_bg,c H_c = I_bg H_full
+    lhs = sum(ib[c] * bank[c, 0] for c in range(8))
+    rhs = np.sum(S * P * P) * bank[8, 0]
+    assert np.allclose(lhs, rhs, atol=1e-12 * np.abs(rhs).max())
+    assert np.allclose(bank[8, 0], tfm.labelfree_3d(o.replace(model=op.LABELFREE_3D))[0],
+                       atol=1e-13 * np.abs(bank[8, 0]).max())
+    # Hermitian: H(-nu) = conj H(nu) for every aperture
+    for c in range(9):
+        H = bank[c, 0]
+        Hm = np.roll(np.flip(H, axis=(0, 1, 2)), 1, axis=(0, 1, 2))
+        assert np.allclose(Hm, np.conj(H), atol=1e-12 * np.abs(H).max())
+
+
+def test_sector_point_response_is_abbe_source_sum():
+    o = lf_optics(model=op.SECTORS9_3D, nz=3, ny=24, nx=24, na_det=0.8, na_ill=0.45,
+                  defocus=0.2, tilt_zenith=0.1, tilt_azimuth=0.3)
+    for c in (0, 3, 6):
+        Sc = op.sector_pupil(o, c)
+        assert np.count_nonzero(Sc) >= 1
+        got = tfm.labelfree_point_response(o, Sc)
+        ref = abbe_point_response(o, Sc)
+        assert np.allclose(got, ref, atol=1e-12 * np.abs(ref).max())
