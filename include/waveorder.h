@@ -46,6 +46,13 @@
  *   POL5_3D         5 x 4, 3D  five polarisation states (swing) through a
  *                   circular analyser; properties [phase, rho cos 2w,
  *                   rho sin 2w, absorption]
+ *   SECTORS9_3D     9 x 1, 3D  multi-aperture phase: channels 0-7 illuminate
+ *                   through the azimuthal sectors [c pi/4, (c+1) pi/4) of the
+ *                   source disc (about its centre; the centre point in sector
+ *                   0), channel 8 through the full disc; each channel's data
+ *                   are relative to its own background (Results,
+ *                   cardiomyocytes; Methods "Cardiomyocyte reconstructions";
+ *                   Fig. 4c's 9 x 1 column)
  */
 #ifndef WAVEORDER_H
 #define WAVEORDER_H
@@ -70,7 +77,8 @@ enum {
   WO_MODEL_FLUOR_3D = 0,
   WO_MODEL_LABELFREE_3D = 1,
   WO_MODEL_LABELFREE_THIN = 2,
-  WO_MODEL_POL5_3D = 3
+  WO_MODEL_POL5_3D = 3,
+  WO_MODEL_SECTORS9_3D = 4
 };
 
 enum {

@@ -23,6 +23,7 @@ MODEL_FLUOR_3D = 0
 MODEL_LABELFREE_3D = 1
 MODEL_LABELFREE_THIN = 2
 MODEL_POL5_3D = 3
+MODEL_SECTORS9_3D = 4
 
 OP_TRANSFER_FUNCTION = 0
 OP_FORWARD = 1

@@ -109,6 +109,7 @@ bool bank_shape(const wo_optics* o, Shape* s) {
     case WO_MODEL_LABELFREE_3D: s->C = 1; s->P = 2; break;
     case WO_MODEL_LABELFREE_THIN: s->C = o->nz; s->P = 2; s->thin = true; s->dims = 2; break;
     case WO_MODEL_POL5_3D: s->C = 5; s->P = 4; break;
+    case WO_MODEL_SECTORS9_3D: s->C = 9; s->P = 1; break;
     default: return false;
   }
   return true;
@@ -120,7 +121,7 @@ long bank_elems(const Shape& s) {
 
 int check_sampling(const wo_optics* o) {
   if (!o) return WO_EINVAL;
-  if (o->model < 0 || o->model > 3) return WO_EINVAL;
+  if (o->model < 0 || o->model > 4) return WO_EINVAL;
   if (!(o->dz > 0 && o->dy > 0 && o->dx > 0 && o->wavelength > 0)) return WO_EINVAL;
   if (!smooth235(o->nz) || !smooth235(o->ny) || !smooth235(o->nx)) return WO_EUNSUPPORTED;
   if (o->nx % 2 || o->ny % 2) return WO_EUNSUPPORTED;
@@ -160,6 +161,33 @@ int check_optics(const wo_optics* o) {
   return WO_OK;
 }
 
+// Every aperture of the 9-aperture model must pass direct light (sum_q S_c P^2 > 0),
+// evaluated with the device's pupil functions.
+bool sectors_lit(const wo_optics& oo) {
+  DevOptics d;
+  memset(&d, 0, sizeof(d));
+  d.wavelength = oo.wavelength;
+  d.na_ill = oo.na_ill;
+  d.n_medium = oo.n_medium;
+  d.tilt_zenith = oo.tilt_zenith;
+  d.tilt_azimuth = oo.tilt_azimuth;
+  double cy, cx;
+  source_centre(d, &cy, &cx);
+  const double dnu = fmin(1.0 / (oo.nx * oo.dx), 1.0 / (oo.ny * oo.dy));
+  const double hw = oo.edge_width * dnu;
+  double bg[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (int ky = 0; ky < oo.ny; ++ky)
+    for (int kx = 0; kx < oo.nx; ++kx) {
+      const double fy = fftfreq(ky, oo.ny, oo.dy), fx = fftfreq(kx, oo.nx, oo.dx);
+      const double P = disc(fy, fx, oo.na_det / oo.wavelength, hw);
+      const double S = disc(fy - cy, fx - cx, oo.na_ill / oo.wavelength, hw);
+      bg[octant(fy - cy, fx - cx)] += S * P * P;
+    }
+  for (double b : bg)
+    if (!(b > 0.0)) return false;
+  return true;
+}
+
 int validate(const wo_optics* o, int32_t n) {
   if (!o || n < 1) return WO_EINVAL;
   int st = check_sampling(&o[0]);
@@ -168,6 +196,7 @@ int validate(const wo_optics* o, int32_t n) {
     if (!same_sampling(&o[0], &o[i])) return WO_EINVAL;
     st = check_optics(&o[i]);
     if (st) return st;
+    if (o[i].model == WO_MODEL_SECTORS9_3D && !sectors_lit(o[i])) return WO_EINVAL;
   }
   return WO_OK;
 }
@@ -232,10 +261,14 @@ size_t partials_bytes(const wo_optics* o, int32_t n) {
   return align_up((size_t)n * ((o->nx + W - 1) / W) * sizeof(double));
 }
 
+// Field sets the TF synthesis generates per patch: one per illumination aperture.
+int field_sets(const wo_optics* o) { return o->model == WO_MODEL_SECTORS9_3D ? 9 : 1; }
+
 size_t tf_ws(const wo_optics* o, int32_t n, const Shape& s) {
   const int nf = o->model == WO_MODEL_FLUOR_3D ? 1 : 2;
-  size_t b = params_bytes(n) + partials_bytes(o, n);
-  b += align_up((size_t)n * nf * s.Z * s.Y * s.X * sizeof(float2));
+  const int nv = n * field_sets(o);
+  size_t b = params_bytes(nv) + partials_bytes(o, nv);
+  b += align_up((size_t)nv * nf * s.Z * s.Y * s.X * sizeof(float2));
   if (o->model == WO_MODEL_POL5_3D) b += align_up((size_t)n * 2 * s.Z * s.Y * s.Xh * sizeof(float2));
   return b;
 }
@@ -396,6 +429,7 @@ double band_count(const wo_optics* o, double nu_c) {
 DevOptics dev_optics(const wo_optics& o) {
   DevOptics d;
   memset(&d, 0, sizeof(d));
+  d.sector = -1;
   d.wavelength = o.wavelength;
   d.na_ill = o.na_ill;
   d.na_det = o.na_det;
@@ -881,31 +915,27 @@ int wo_transfer_function(const wo_optics* o, int32_t n, void* tf_out, void* ws, 
   bank_shape(o, &s);
   if (ws_bytes < tf_ws(o, n, s)) return WO_ENOMEM;
   hipStream_t hs = (hipStream_t)stream;
-  std::vector<DevOptics> h(n);
-  for (int i = 0; i < n; ++i) {
-    DevOptics& d = h[i];
-    memset(&d, 0, sizeof(d));
-    d.wavelength = o[i].wavelength;
-    d.na_ill = o[i].na_ill;
-    d.na_det = o[i].na_det;
-    d.n_medium = o[i].n_medium;
-    d.defocus = o[i].defocus;
-    d.tilt_zenith = o[i].tilt_zenith;
-    d.tilt_azimuth = o[i].tilt_azimuth;
-    d.edge_width = o[i].edge_width;
-    if (o[i].model == WO_MODEL_POL5_3D) pol5_kappa(o[i].swing, d.kappa);
-  }
+  const int fs = field_sets(o);
+  const int nv = n * fs;          // field sets: patch i, aperture c at i * fs + c
+  std::vector<DevOptics> h(nv);
+  for (int i = 0; i < n; ++i)
+    for (int c = 0; c < fs; ++c) {
+      DevOptics& d = h[i * fs + c];
+      d = dev_optics(o[i]);
+      if (fs == 9) d.sector = c < 8 ? c : -1;
+      if (o[i].model == WO_MODEL_POL5_3D) pol5_kappa(o[i].swing, d.kappa);
+    }
   char* w = (char*)ws;
   DevOptics* dopt = (DevOptics*)w;
-  w += params_bytes(n);
+  w += params_bytes(nv);
   double* partials = (double*)w;
-  w += partials_bytes(o, n);
+  w += partials_bytes(o, nv);
   const int nf = o->model == WO_MODEL_FLUOR_3D ? 1 : 2;
   float2* ab = (float2*)w;
-  w += align_up((size_t)n * nf * s.Z * s.Y * s.X * sizeof(float2));
-  WO_TRY(launch_set_params(dopt, h.data(), n, hs));
+  w += align_up((size_t)nv * nf * s.Z * s.Y * s.X * sizeof(float2));
+  WO_TRY(launch_set_params(dopt, h.data(), nv, hs));
   const Sampling sm = sampling_of(o);
-  WO_TRY(launch_tf_fields_y(dopt, sm, n, ab, partials, hs));
+  WO_TRY(launch_tf_fields_y(dopt, sm, nv, ab, partials, hs));
   float2* tf = (float2*)tf_out;
   const long M = s.Y * s.Xh;
   const long plane = s.Y * s.Xh;
@@ -923,6 +953,12 @@ int wo_transfer_function(const wo_optics* o, int32_t n, void* tf_out, void* ws, 
     case WO_MODEL_LABELFREE_THIN:
       WO_TRY(launch_tf_rows_labelfree(partials, sm, n, ab, tf, 2 * s.Z * plane, plane, 2 * plane, hs));
       WO_TRY(launch_cols(tf, (int)s.Y, s.Xh, 2 * s.Z, 2 * s.Z, n, -1.f, hs, "k_cols_y_tf"));
+      break;
+    case WO_MODEL_SECTORS9_3D:
+      // phase TF of every aperture: [patch][aperture][1][Z][Y][Xh]
+      WO_TRY(launch_tf_rows_labelfree(partials, sm, nv, ab, tf, s.Z * plane, -1, plane, hs));
+      WO_TRY(launch_cols(tf, (int)s.Y, s.Xh, s.Z, s.Z, nv, -1.f, hs, "k_cols_y_tf"));
+      WO_TRY(launch_cols(tf, (int)s.Z, M, 1, 1, nv, -1.f, hs, "k_cols_z_tf"));
       break;
     case WO_MODEL_POL5_3D: {
       float2* uw = (float2*)w;

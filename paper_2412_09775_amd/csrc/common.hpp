@@ -368,7 +368,7 @@ __device__ __forceinline__ long xcd_block() {
 
 // ---------------------------------------------------------------- optics
 
-enum Model { kFluor3D = 0, kLabelFree3D = 1, kLabelFreeThin = 2, kPol5 = 3 };
+enum Model { kFluor3D = 0, kLabelFree3D = 1, kLabelFreeThin = 2, kPol5 = 3, kSectors9 = 4 };
 
 // Per-patch optical parameters on the device (float64).  ``ibg`` is written
 // by the pupil-sum kernel: sum S P^2 (label-free) or sum P^2 (fluorescence).
@@ -378,8 +378,20 @@ struct DevOptics {
   double edge_width;       // half-width of the soft edge, in frequency pixels
   double kappa[5][4][2];   // polarisation coupling (re, im), pol5 only
   double ibg;
-  double pad[3];
+  int sector;              // illumination aperture: -1 the full disc, 0..7 an azimuthal sector
+  int ipad;
+  double pad[2];
 };
+
+// Azimuthal sector k of the direction (dy, dx): the azimuth, from +x towards +y,
+// lies in [k pi/4, (k+1) pi/4); the origin is in sector 0.  Comparisons only.
+__host__ __device__ __forceinline__ int octant(double dy, double dx) {
+  if (dy == 0.0 && dx == 0.0) return 0;
+  if (dy >= 0.0 && dx > 0.0) return dy < dx ? 0 : 1;
+  if (dx <= 0.0 && dy > 0.0) return dy > -dx ? 2 : 3;
+  if (dy <= 0.0 && dx < 0.0) return dy > dx ? 4 : 5;
+  return dx < -dy ? 6 : 7;
+}
 
 // Auto-tune state of one (virtual) patch: Adam moments and hyper-parameters,
 // Tikhonov eta, the mid-band cutoff and band size, and the last loss/gradient.
@@ -399,13 +411,13 @@ struct Sampling {
   double dz, dy, dx;
 };
 
-__device__ __forceinline__ double fftfreq(int k, int n, double d) {
+__host__ __device__ __forceinline__ double fftfreq(int k, int n, double d) {
   const double val = 1.0 / ((double)n * d);
   const int ks = (k < (n + 1) / 2) ? k : k - n;
   return (double)ks * val;
 }
 
-__device__ __forceinline__ double edge_profile(double inside, double hw) {
+__host__ __device__ __forceinline__ double edge_profile(double inside, double hw) {
   if (hw == 0.0) return inside >= 0.0 ? 1.0 : 0.0;
   double t = (inside / hw + 1.0) * 0.5;
   t = t < 0.0 ? 0.0 : (t > 1.0 ? 1.0 : t);
@@ -420,7 +432,7 @@ __device__ __forceinline__ double edge_slope(double inside, double hw) {
   return 6.0 * t * (1.0 - t) * (0.5 / hw);
 }
 
-__device__ __forceinline__ double disc(double fy, double fx, double radius, double hw) {
+__host__ __device__ __forceinline__ double disc(double fy, double fx, double radius, double hw) {
   const double r2 = fy * fy + fx * fx;
   if (hw == 0.0) return r2 <= radius * radius ? 1.0 : 0.0;
   return edge_profile(radius - sqrt(r2), hw);
@@ -431,7 +443,7 @@ __device__ __forceinline__ double soft_halfwidth(const DevOptics& o, const Sampl
   return o.edge_width * dnu;
 }
 
-__device__ __forceinline__ void source_centre(const DevOptics& o, double* cy, double* cx) {
+__host__ __device__ __forceinline__ void source_centre(const DevOptics& o, double* cy, double* cx) {
   const double r = o.n_medium * sin(o.tilt_zenith) / o.wavelength;
   *cy = r * sin(o.tilt_azimuth);
   *cx = r * cos(o.tilt_azimuth);

@@ -138,7 +138,8 @@ __global__ __launch_bounds__(1024) void k_tf_fields_y(const DevOptics* __restric
               sp[i] = P;
               psum += P * P;
             } else {
-              const double S = disc(fy - cy, fx - cx, ri, hw);
+              double S = disc(fy - cy, fx - cx, ri, hw);
+              if (o.sector >= 0 && octant(fy - cy, fx - cx) != o.sector) S = 0.0;
               psum += S * P * P;
               sp[i] = S * P;
               if (kz > 0.0) gg[i] = P * km / kz;   // P * (i k_m / kz)
@@ -248,6 +249,7 @@ hipError_t launch_tf_fields_y(const DevOptics* opt, const Sampling& sm, int npat
 // ------------------------------------------------------------------ rows: label-free
 
 // out[patch * patch_stride + p * pstride + z * zstride + y * Xh + k], p = 0 phase, 1 absorption
+// (pstride < 0: phase only)
 __device__ __forceinline__ double pupil_total(const double* partials, long tiles_x) {
   double t = 0.0;
   for (long i = 0; i < tiles_x; ++i) t += partials[i];
@@ -312,7 +314,7 @@ __global__ __launch_bounds__(1024) void k_tf_rows_lf(const double* __restrict__ 
     const float2 U = make_float2(Ck.x + Cm.x, Ck.y - Cm.y);          // C + conj(C(-k))
     const float2 V = make_float2(-(Ck.y + Cm.y), Ck.x - Cm.x);       // i (C - conj(C(-k)))
     op[(long)z * zstride + (long)y * Xh + k] = U;
-    op[pstride + (long)z * zstride + (long)y * Xh + k] = V;
+    if (pstride >= 0) op[pstride + (long)z * zstride + (long)y * Xh + k] = V;
   }
 }
 

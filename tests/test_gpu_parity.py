@@ -53,6 +53,12 @@ def pol5(nz=16, ny=64, nx=64, **kw):
     return o.replace(**kw)
 
 
+def sectors(nz=16, ny=64, nx=64, **kw):
+    o = op.Optics(model=op.SECTORS9_3D, nz=nz, ny=ny, nx=nx, dz=0.2, dy=0.1, dx=0.1,
+                  wavelength=0.532, na_ill=0.5, na_det=1.2, n_medium=1.33)
+    return o.replace(**kw)
+
+
 def thin(nz=32, ny=128, nx=128, **kw):
     o = op.Optics(model=op.LABELFREE_THIN, nz=nz, ny=ny, nx=nx, dz=0.2, dy=0.1, dx=0.1,
                   wavelength=0.532, na_ill=0.5, na_det=1.2, n_medium=1.33, edge_width=0.5)
@@ -77,6 +83,13 @@ CASES = {
     "labelfree_rows_4096": [labelfree(nz=2, ny=8, nx=4096)],
     "fluor_depth_4096": [fluor(nz=4096, ny=8, nx=8, dz=0.25)],
     "pol5_ragged": [pol5(nz=12, ny=40, nx=50, tilt_zenith=0.1)],
+    # 9 apertures (8 azimuthal sectors + the full disc) x phase; a tilted, soft-edged
+    # batch of two with uncompiled lengths
+    "sectors9": [sectors()],
+    "sectors9_tilt_soft_batch2": [sectors(nz=12, ny=48, nx=40, defocus=0.2, tilt_zenith=0.2,
+                                          tilt_azimuth=0.5, edge_width=0.5),
+                                  sectors(nz=12, ny=48, nx=40, na_det=1.1, tilt_zenith=0.05,
+                                          edge_width=0.5)],
 }
 
 
@@ -93,6 +106,8 @@ def specimen(o, seed):
         return synth.ellipsoids((o.nz, o.ny, o.nx), (o.dz, o.dy, o.dx), 12, seed, semi_axes=(0.5, 1.5))
     if o.model == op.POL5_3D:
         return synth.fibres((o.nz, o.ny, o.nx), (o.dz, o.dy, o.dx), 6, seed)
+    if o.model == op.SECTORS9_3D:
+        return synth.ellipsoids((o.nz, o.ny, o.nx), (o.dz, o.dy, o.dx), 12, seed, semi_axes=(0.5, 1.5))[:1]
     return synth.thin_cells((o.ny, o.nx), o.dx, 8, seed)
 
 
@@ -113,6 +128,18 @@ def test_edges_are_decided_identically(name):
     for o in CASES[name]:
         if o.edge_width == 0:
             assert op.hard_edge_margin(o) > 1e-9
+        if o.model == op.SECTORS9_3D and o.tilt_zenith != 0:
+            # lattice points sit on a sector boundary (an axis or diagonal through the
+            # tilted centre) exactly -- decided alike everywhere -- or keep away from it,
+            # so FP64 rounding of the centre cannot flip a decision
+            fy, fx = op.lateral_frequencies(o)
+            cy, cx = op.source_centre(o)
+            dy, dx = fy - cy, fx - cx
+            r = np.hypot(dy, dx) + 1e-300
+            inside = r <= o.na_ill / o.wavelength + o.edge_width * o.dnu
+            for g in (dy, dx, dy - dx, dy + dx):
+                m = np.abs(g[inside]) / r[inside]
+                assert np.all((g[inside] == 0) | (m > 1e-9))
 
 
 @pytest.mark.parametrize("name", list(CASES))
