@@ -67,11 +67,22 @@ struct GatherIm2col {
     return r;
   }
   __device__ __forceinline__ int chans() const { return g.C; }
-  __device__ __forceinline__ u16 at(const Row& r, TapCh t) const {
+  __device__ __forceinline__ const u16* ptr(const Row& r, TapCh t) const {
     const int kw = t.tap % 3, kh = (t.tap / 3) % 3, kd = t.tap / 9;
     const int id = r.d0 + kd, ih = r.h0 + kh, iw = r.w0 + kw;
-    if (id < 0 || id >= g.D || ih < 0 || ih >= g.H || iw < 0 || iw >= g.W) return 0;
-    return x[(((r.n * g.D + id) * g.H + ih) * g.W + iw) * g.C + t.ch];
+    if (id < 0 || id >= g.D || ih < 0 || ih >= g.H || iw < 0 || iw >= g.W) return nullptr;
+    return x + (((r.n * g.D + id) * g.H + ih) * g.W + iw) * g.C + t.ch;
+  }
+  __device__ __forceinline__ u16 at(const Row& r, TapCh t) const {
+    const u16* p = ptr(r, t);
+    return p ? *p : (u16)0;
+  }
+  // 8 consecutive k (channels t.ch .. t.ch + 7 of one tap), when g.C % 8 == 0
+  static constexpr int kMode = 1;
+  __host__ __device__ __forceinline__ bool vec() const { return g.C % 8 == 0; }
+  __device__ __forceinline__ uint4 load8(const Row& r, TapCh t) const {
+    const u16* p = ptr(r, t);
+    return p ? *(const uint4*)p : make_uint4(0, 0, 0, 0);
   }
 };
 
@@ -84,6 +95,11 @@ struct GatherRows {
   __device__ __forceinline__ Row row(long n) const { return Row{w + n * K}; }
   __device__ __forceinline__ int chans() const { return C; }
   __device__ __forceinline__ u16 at(const Row& r, TapCh t) const { return r.p[(long)t.tap * C + t.ch]; }
+  static constexpr int kMode = 1;
+  __host__ __device__ __forceinline__ bool vec() const { return C % 8 == 0; }
+  __device__ __forceinline__ uint4 load8(const Row& r, TapCh t) const {
+    return *(const uint4*)(r.p + (long)t.tap * C + t.ch);
+  }
 };
 
 // A(m, k) of the input-gradient GEMM restricted to one parity class of input
@@ -108,14 +124,24 @@ struct GatherCol2imClass {
     return r;
   }
   __device__ __forceinline__ int chans() const { return g.C; }
-  __device__ __forceinline__ u16 at(const Row& r, TapCh t) const {
+  __device__ __forceinline__ const u16* ptr(const Row& r, TapCh t) const {
     const int jw = t.tap % nw, jh = (t.tap / nw) % nh, jd = t.tap / (nw * nh);
     const int kd = nd == 1 ? 1 : 2 * jd, kh = nh == 1 ? 1 : 2 * jh, kw = nw == 1 ? 1 : 2 * jw;
     const int od2 = r.d + 1 - kd, oh2 = r.h + 1 - kh, ow2 = r.w + 1 - kw;
-    if (od2 < 0 || oh2 < 0 || ow2 < 0) return 0;
+    if (od2 < 0 || oh2 < 0 || ow2 < 0) return nullptr;
     const int od = od2 >> 1, oh = oh2 >> 1, ow = ow2 >> 1;
-    if (od >= g.Do || oh >= g.Ho || ow >= g.Wo) return 0;
-    return gz[(((r.n * g.Do + od) * g.Ho + oh) * g.Wo + ow) * g.C + t.ch];
+    if (od >= g.Do || oh >= g.Ho || ow >= g.Wo) return nullptr;
+    return gz + (((r.n * g.Do + od) * g.Ho + oh) * g.Wo + ow) * g.C + t.ch;
+  }
+  __device__ __forceinline__ u16 at(const Row& r, TapCh t) const {
+    const u16* p = ptr(r, t);
+    return p ? *p : (u16)0;
+  }
+  static constexpr int kMode = 1;
+  __host__ __device__ __forceinline__ bool vec() const { return g.C % 8 == 0; }
+  __device__ __forceinline__ uint4 load8(const Row& r, TapCh t) const {
+    const u16* p = ptr(r, t);
+    return p ? *(const uint4*)p : make_uint4(0, 0, 0, 0);
   }
   // the global input position of class row m (output row mapping)
   __device__ __forceinline__ long out_row(long m) const {
@@ -132,11 +158,18 @@ struct GatherWTClass {
   struct Row { int ci; };
   __device__ __forceinline__ Row row(long n) const { return Row{(int)n}; }
   __device__ __forceinline__ int chans() const { return Cout; }
-  __device__ __forceinline__ u16 at(const Row& r, TapCh t) const {
+  __device__ __forceinline__ long off(TapCh t) const {
     const int jw = t.tap % nw, jh = (t.tap / nw) % nh, jd = t.tap / (nw * nh);
     const int kd = nd == 1 ? 1 : 2 * jd, kh = nh == 1 ? 1 : 2 * jh, kw = nw == 1 ? 1 : 2 * jw;
     const int tap = (kd * 3 + kh) * 3 + kw;
-    return w[((long)t.ch * 27 + tap) * Cin + r.ci];
+    return ((long)t.ch * 27 + tap) * Cin;
+  }
+  __device__ __forceinline__ u16 at(const Row& r, TapCh t) const { return w[off(t) + r.ci]; }
+  // 8 consecutive rows (ci .. ci + 7) at one k, when Cin % 8 == 0
+  static constexpr int kMode = 2;
+  __host__ __device__ __forceinline__ bool vec() const { return Cin % 8 == 0; }
+  __device__ __forceinline__ uint4 load_rows8(long n0, TapCh t) const {
+    return *(const uint4*)(w + off(t) + n0);
   }
 };
 
@@ -149,6 +182,11 @@ struct GatherT {
   __device__ __forceinline__ Row row(long m) const { return Row{(int)m}; }
   __device__ __forceinline__ int chans() const { return 1; }
   __device__ __forceinline__ u16 at(const Row& r, TapCh t) const { return gz[(long)t.tap * Cout + r.co]; }
+  static constexpr int kMode = 2;
+  __host__ __device__ __forceinline__ bool vec() const { return Cout % 8 == 0; }
+  __device__ __forceinline__ uint4 load_rows8(long m0, TapCh t) const {
+    return *(const uint4*)(gz + (long)t.tap * Cout + m0);
+  }
 };
 
 // B(k, n) of the weight-gradient GEMM: im2col(x)(position k, n = tap * Cin + ci).
@@ -159,6 +197,13 @@ struct GatherIm2colT {
   __device__ __forceinline__ int chans() const { return 1; }
   __device__ __forceinline__ u16 at(const Row& r, TapCh t) const {
     return a.at(a.row(t.tap), TapCh{r.tap, r.ci});
+  }
+  // rows n0 .. n0 + 7 (channels of one tap) at position k, when Cin % 8 == 0
+  static constexpr int kMode = 2;
+  __host__ __device__ __forceinline__ bool vec() const { return a.g.C % 8 == 0; }
+  __device__ __forceinline__ uint4 load_rows8(long n0, TapCh t) const {
+    const Row r = row(n0);
+    return a.load8(a.row(t.tap), TapCh{r.tap, r.ci});
   }
 };
 
@@ -175,7 +220,42 @@ struct ClassRows {
 constexpr int kBM = 64, kBN = 64, kBK = 32, kLdsPad = 8;
 
 // C_z[rowmap(m)][n] = sum_{k in chunk z} A(m, k) B(k, n); C_z = C + z * Mout * N.
-template <class GA, class GB, class RM>
+// Operand tiles are staged in LDS as [row][k].  Load modes per operand: 0 one
+// element at a time; 1 eight consecutive k of a row in one 16-byte load; 2 eight
+// consecutive rows at one k in one 16-byte load (the operand is contiguous along
+// its rows).
+template <class G, int MODE>
+__device__ __forceinline__ void stage_tile(const G& g, const typename G::Row& r, bool row_ok,
+                                           bool rows8_ok, long row8, long k0, long kend, int lk,
+                                           int kk, int lr, int lr8, int ch,
+                                           u16 (*T)[kBK + kLdsPad]) {
+  if constexpr (MODE == 2) {
+    const long k = k0 + kk;
+    uint4 v = make_uint4(0, 0, 0, 0);
+    if (rows8_ok && k < kend) v = g.load_rows8(row8, TapCh{(int)(k / ch), (int)(k % ch)});
+    const u16* pv = (const u16*)&v;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) T[lr8 + i][kk] = pv[i];
+  } else if constexpr (MODE == 1) {
+    const long kf = k0 + lk;
+    uint4 v = make_uint4(0, 0, 0, 0);
+    if (row_ok && kf < kend) v = g.load8(r, TapCh{(int)(kf / ch), (int)(kf % ch)});
+    *(uint4*)&T[lr][lk] = v;
+  } else {
+    const long kf = k0 + lk;
+    TapCh tc{(int)(kf / ch), (int)(kf % ch)};
+    u16 v[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      v[i] = (row_ok && kf + i < kend) ? g.at(r, tc) : (u16)0;
+      if (++tc.ch == ch) { tc.ch = 0; ++tc.tap; }
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) T[lr][lk + i] = v[i];
+  }
+}
+
+template <class GA, class GB, class RM, int AM, int BM>
 __global__ __launch_bounds__(256) void k_gemm_bf16(GA ga, GB gb, RM rowmap, float* __restrict__ C,
                                                    long M, long N, long K, long kchunk, long Mout) {
   __shared__ __attribute__((aligned(16))) u16 As[kBM][kBK + kLdsPad];
@@ -190,29 +270,17 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GA ga, GB gb, RM rowmap, floa
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  // modes 0, 1: row lr, k offset lk (8 consecutive); mode 2: rows lr8 .. lr8 + 7, k offset kk
   const int lr = t >> 2, lk = (t & 3) * 8;
+  const int kk = t & 31, lr8 = (t >> 5) * 8;
   const bool am = m0 + lr < M, bn = n0 + lr < N;
+  const bool am8 = m0 + lr8 < M, bn8 = n0 + lr8 < N;
   const typename GA::Row ra = ga.row(am ? m0 + lr : 0);
   const typename GB::Row rb = gb.row(bn ? n0 + lr : 0);
   const int ca = ga.chans(), cb = gb.chans();
   for (long k0 = kbeg; k0 < kend; k0 += kBK) {
-    const long kf = k0 + lk;
-    TapCh ta{(int)(kf / ca), (int)(kf % ca)};
-    TapCh tb{(int)(kf / cb), (int)(kf % cb)};
-    u16 va[8], vb[8];
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      const bool kin = kf + i < kend;
-      va[i] = (am && kin) ? ga.at(ra, ta) : (u16)0;
-      vb[i] = (bn && kin) ? gb.at(rb, tb) : (u16)0;
-      if (++ta.ch == ca) { ta.ch = 0; ++ta.tap; }
-      if (++tb.ch == cb) { tb.ch = 0; ++tb.tap; }
-    }
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      As[lr][lk + i] = va[i];
-      Bs[lr][lk + i] = vb[i];
-    }
+    stage_tile<GA, AM>(ga, ra, am, am8, m0 + lr8, k0, kend, lk, kk, lr, lr8, ca, As);
+    stage_tile<GB, BM>(gb, rb, bn, bn8, n0 + lr8, k0, kend, lk, kk, lr, lr8, cb, Bs);
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
@@ -241,6 +309,12 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GA ga, GB gb, RM rowmap, floa
     }
 }
 
+// Every gather states its vector mode (kMode) and when it applies (vec()).
+template <class G>
+static int load_mode(const G& g) {
+  return g.vec() ? G::kMode : 0;
+}
+
 template <class GA, class GB, class RM = IdentityRows>
 static hipError_t gemm(GA ga, GB gb, float* C, long M, long N, long K, int splits, hipStream_t s,
                        const char* tag, RM rowmap = RM(), long Mout = -1) {
@@ -248,9 +322,17 @@ static hipError_t gemm(GA ga, GB gb, float* C, long M, long N, long K, int split
   kchunk = (kchunk + kBK - 1) / kBK * kBK;
   const int z = (int)((K + kchunk - 1) / kchunk);
   dim3 grid((unsigned)((M + kBM - 1) / kBM), (unsigned)((N + kBN - 1) / kBN), (unsigned)z);
-  { ScopedTiming _t(tag, s);
-  hipLaunchKernelGGL((k_gemm_bf16<GA, GB, RM>), grid, dim3(256), 0, s, ga, gb, rowmap, C, M, N, K,
-                     kchunk, Mout < 0 ? M : Mout); }
+  const int am = load_mode(ga), bm = load_mode(gb);
+  const long mo = Mout < 0 ? M : Mout;
+  ScopedTiming _t(tag, s);
+#define WO_GEMM(A_, B_)                                                                            \
+  hipLaunchKernelGGL((k_gemm_bf16<GA, GB, RM, A_, B_>), grid, dim3(256), 0, s, ga, gb, rowmap, C, M, \
+                     N, K, kchunk, mo)
+  if (am && bm) WO_GEMM(GA::kMode, GB::kMode);
+  else if (am) WO_GEMM(GA::kMode, 0);
+  else if (bm) WO_GEMM(0, GB::kMode);
+  else WO_GEMM(0, 0);
+#undef WO_GEMM
   return hipGetLastError();
 }
 
@@ -552,8 +634,12 @@ int cnn_run(const float* params, const float* x, int N, int Z, int Y, int X, con
   float* lossp = dy + (long)N * kCnnOut;
   float* feat = lossp + N;
   const int Cf = kCnnChannels[kCnnLayers];
+  { ScopedTiming _tm("k_to_bf16", s);
   hipLaunchKernelGGL(k_to_bf16, dim3(blocks(net.nparam, 256)), dim3(256), 0, s, params, net.nparam, pbf);
+  }
+  { ScopedTiming _tm("k_normalise", s);
   hipLaunchKernelGGL(k_normalise, dim3(N), dim3(256), 0, s, x, (long)Z * Y * X, xb);
+  }
   WO_HIP_CHECK(hipGetLastError());
   const u16* a_in = xb;
   for (int l = 0; l < kCnnLayers; ++l) {
@@ -563,32 +649,44 @@ int cnn_run(const float* params, const float* x, int N, int Z, int Y, int X, con
                       K, 1, s, "k_gemm_conv_fwd"));
     float* z = (float*)(w + W.z[l]);
     u16* a = (u16*)(w + W.a[l]);
+    { ScopedTiming _tm("k_bias_gelu", s);
     hipLaunchKernelGGL(k_bias_gelu, dim3(blocks(L.P_out * L.Cout, 256)), dim3(256), 0, s, C,
                        params + L.b_off, L.P_out, L.Cout, z, a);
+    }
     a_in = a;
   }
+  { ScopedTiming _tm("k_head", s);
   hipLaunchKernelGGL(k_head, dim3(N), dim3(256), 0, s, a_in, net.npos_last, Cf, params + net.wh_off,
                      params + net.bh_off, target, N, y_out, feat, dy, lossp, ga);
+  }
   WO_HIP_CHECK(hipGetLastError());
   if (!target) return WO_OK;
+  { ScopedTiming _tm("k_head_grads", s);
   hipLaunchKernelGGL(k_head_grads, dim3(1), dim3(256), 0, s, dy, feat, lossp, N, Cf,
                      grad + net.wh_off, grad + net.bh_off, loss_out);
+  }
   for (int l = kCnnLayers - 1; l >= 0; --l) {
     const Layer& L = net.L[l];
     const long K = 27L * L.Cin;
     const float* z = (const float*)(w + W.z[l]);
+    { ScopedTiming _tm("k_gelu_bwd", s);
     hipLaunchKernelGGL(k_gelu_bwd, dim3(blocks(L.P_out * L.Cout, 256)), dim3(256), 0, s, ga, z,
                        L.P_out * L.Cout, gz);
+    }
+    { ScopedTiming _tm("k_bias_grad", s);
     hipLaunchKernelGGL(k_bias_grad, dim3(L.Cout), dim3(256), 0, s, gz, L.P_out, L.Cout,
                        grad + L.b_off);
+    }
     const u16* a_prev = l == 0 ? xb : (const u16*)(w + W.a[l - 1]);
     // weight gradient, split over output positions
     const int splits = wgrad_splits(L.P_out);
     const int zs = splits_used(L.P_out, splits);
     WO_HIP_CHECK(gemm(GatherT{gz, L.Cout}, GatherIm2colT{GatherIm2col{a_prev, L.g}}, part, L.Cout, K,
                       L.P_out, splits, s, "k_gemm_conv_wgrad"));
+    { ScopedTiming _tm("k_sum_splits", s);
     hipLaunchKernelGGL(k_sum_splits, dim3(blocks((long)L.Cout * K, 256)), dim3(256), 0, s, part, zs,
                        (long)L.Cout * K, grad + L.w_off);
+    }
     if (l > 0) {
       ConvGeom gd = L.g;
       gd.C = L.Cout;
@@ -602,8 +700,10 @@ int cnn_run(const float* params, const float* x, int N, int Z, int Y, int X, con
 hipError_t cnn_adamw(float* p, const float* g, float* m, float* v, long n, int t, float lr, float wd,
                      void* ws_pbf, hipStream_t s) {
   const float c1 = 1.f - powf(0.9f, (float)t), c2 = 1.f - powf(0.999f, (float)t);
+  { ScopedTiming _tm("k_adamw", s);
   hipLaunchKernelGGL(k_adamw, dim3(blocks(n, 256)), dim3(256), 0, s, p, g, m, v, n, lr, wd, c1, c2,
                      (u16*)ws_pbf);
+  }
   return hipGetLastError();
 }
 
