@@ -363,13 +363,48 @@ static int splits_used(long K, int splits) {
   return (int)((K + kchunk - 1) / kchunk);
 }
 
-// out[i] = sum_z part[z * n + i] (fixed order)
-__global__ void k_sum_splits(const float* __restrict__ part, int z, long n, float* __restrict__ out) {
-  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  float s = 0.f;
-  for (int q = 0; q < z; ++q) s += part[q * n + i];
-  out[i] = s;
+// out[i] = sum_q part[q * n + i] for q < z, in a fixed order: a workgroup
+// takes CW consecutive outputs and 256 / CW phases; phase h adds q = h, h + PH,
+// ... with four independent accumulators (loads in flight), then a tree over
+// the phases.  Many phases per output keep the serial chains short when n is
+// small and z large.
+static inline unsigned blocks(long n, int t) { return (unsigned)((n + t - 1) / t); }
+
+template <int CW>
+__global__ __launch_bounds__(256) void k_reduce_parts(const float* __restrict__ part, int z, long n,
+                                                      float* __restrict__ out) {
+  constexpr int PH = 256 / CW;
+  __shared__ float red[256];
+  const int t = threadIdx.x, c = t % CW, h = t / CW;
+  const long i = (long)blockIdx.x * CW + c;
+  float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
+  if (i < n) {
+    int q = h;
+    for (; q + 3 * PH < z; q += 4 * PH) {
+      a0 += part[(long)q * n + i];
+      a1 += part[(long)(q + PH) * n + i];
+      a2 += part[(long)(q + 2 * PH) * n + i];
+      a3 += part[(long)(q + 3 * PH) * n + i];
+    }
+    for (; q < z; q += PH) a0 += part[(long)q * n + i];
+  }
+  red[t] = (a0 + a1) + (a2 + a3);
+  __syncthreads();
+  for (int st = PH / 2; st > 0; st >>= 1) {
+    if (h < st) red[t] += red[t + st * CW];
+    __syncthreads();
+  }
+  if (h == 0 && i < n) out[i] = red[c];
+}
+
+static hipError_t reduce_parts(const float* part, int z, long n, float* out, hipStream_t s) {
+  if (n >= 64L * 512)
+    hipLaunchKernelGGL(k_reduce_parts<64>, dim3(blocks(n, 64)), dim3(256), 0, s, part, z, n, out);
+  else if (n >= 16L * 256)
+    hipLaunchKernelGGL(k_reduce_parts<16>, dim3(blocks(n, 16)), dim3(256), 0, s, part, z, n, out);
+  else
+    hipLaunchKernelGGL(k_reduce_parts<4>, dim3(blocks(n, 4)), dim3(256), 0, s, part, z, n, out);
+  return hipGetLastError();
 }
 
 // ------------------------------------------------------------------ elementwise
@@ -389,47 +424,81 @@ __global__ void k_bias_gelu(const float* C, const float* __restrict__ b, long P,
   a[i] = f2bf(gelu_f(v));
 }
 
-// gz = BF16(ga * GELU'(z))
-__global__ void k_gelu_bwd(const float* __restrict__ ga, const float* __restrict__ z, long n,
-                           u16* __restrict__ gz) {
-  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  gz[i] = f2bf(ga[i] * gelu_grad_f(z[i]));
-}
-
-// gb[c] = sum_p gz[p][c], one workgroup per channel (fixed order)
-__global__ __launch_bounds__(256) void k_bias_grad(const u16* __restrict__ gz, long P, int Co,
-                                                   float* __restrict__ gb) {
+// gz = BF16(ga * GELU'(z)) over P positions x Co channels (Co divides 256), and
+// the bias gradient's first stage: workgroup g sums the rounded gz of its rows
+// [g R, g R + R) per channel in a fixed order into part[g][c].  Lanes run along
+// the channels, so every load and store is coalesced.
+__global__ __launch_bounds__(256) void k_gelu_bwd_bias(const float* __restrict__ ga,
+                                                       const float* __restrict__ z, long P, int Co,
+                                                       long R, u16* __restrict__ gz,
+                                                       float* __restrict__ part) {
   __shared__ float red[256];
-  const int c = blockIdx.x;
+  const int t = threadIdx.x, step = 256 / Co;
+  const int c = t % Co;
+  const long r0 = (long)blockIdx.x * R, r1 = min(P, r0 + R);
   float s = 0.f;
-  for (long p = threadIdx.x; p < P; p += blockDim.x) s += bf2f(gz[p * Co + c]);
-  red[threadIdx.x] = s;
-  __syncthreads();
-  for (int st = 128; st > 0; st >>= 1) {
-    if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
-    __syncthreads();
+  for (long p = r0 + t / Co; p < r1; p += step) {
+    const long i = p * Co + c;
+    const u16 b = f2bf(ga[i] * gelu_grad_f(z[i]));
+    gz[i] = b;
+    s += bf2f(b);
   }
-  if (threadIdx.x == 0) gb[c] = red[0];
+  red[t] = s;
+  __syncthreads();
+  if (t < Co) {
+    float acc = 0.f;
+    for (int k = 0; k < step; ++k) acc += red[k * Co + t];
+    part[(long)blockIdx.x * Co + t] = acc;
+  }
 }
 
-// Per-sample input scaling x / rms(x) -> BF16 channels-last (C = 1).
-__global__ __launch_bounds__(256) void k_normalise(const float* __restrict__ x, long vol,
-                                                   u16* __restrict__ out) {
+// Rows per workgroup of k_gelu_bwd_bias: a multiple of 256 / Co, at most
+// kBiasPartsMax workgroups.
+constexpr int kBiasPartsMax = 1024;
+static long bias_rows(long P, int Co) {
+  const long step = 256 / Co;
+  long R = std::max<long>(4 * step, (P + kBiasPartsMax - 1) / kBiasPartsMax);
+  return (R + step - 1) / step * step;
+}
+
+// Per-sample input scaling x / rms(x) -> BF16 channels-last (C = 1), in two
+// steps so that every sample spreads over many workgroups: FP64 sums of squares
+// of kNormSlices slices per sample, then the scaling, each workgroup adding its
+// sample's slice sums in a fixed order.
+constexpr int kNormSlices = 32;
+__global__ __launch_bounds__(256) void k_sumsq_slices(const float* __restrict__ x, long vol,
+                                                      double* __restrict__ part) {
   __shared__ double red[256];
-  const long n = blockIdx.x;
+  const long n = blockIdx.y;
+  const long len = (vol + kNormSlices - 1) / kNormSlices;
+  const long i0 = blockIdx.x * len, i1 = min(vol, i0 + len);
   const float* xs = x + n * vol;
   double s = 0.0;
-  for (long i = threadIdx.x; i < vol; i += blockDim.x) s += (double)xs[i] * xs[i];
+  for (long i = i0 + threadIdx.x; i < i1; i += blockDim.x) s += (double)xs[i] * xs[i];
   red[threadIdx.x] = s;
   __syncthreads();
   for (int st = 128; st > 0; st >>= 1) {
     if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
     __syncthreads();
   }
-  const double rms = sqrt(red[0] / (double)vol);
-  const float inv = rms > 0.0 ? (float)(1.0 / rms) : 1.f;
-  for (long i = threadIdx.x; i < vol; i += blockDim.x) out[n * vol + i] = f2bf(xs[i] * inv);
+  if (threadIdx.x == 0) part[n * kNormSlices + blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(256) void k_scale_bf16(const float* __restrict__ x, long vol,
+                                                    const double* __restrict__ part,
+                                                    u16* __restrict__ out) {
+  __shared__ float inv_s;
+  const long n = blockIdx.y;
+  if (threadIdx.x == 0) {
+    double ss = 0.0;
+    for (int k = 0; k < kNormSlices; ++k) ss += part[n * kNormSlices + k];
+    const double rms = sqrt(ss / (double)vol);
+    inv_s = rms > 0.0 ? (float)(1.0 / rms) : 1.f;
+  }
+  __syncthreads();
+  const float inv = inv_s;
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < vol) out[n * vol + i] = f2bf(x[n * vol + i] * inv);
 }
 
 // Head per sample: feat = mean over positions of a (BF16), y = Wh feat + bh.
@@ -527,7 +596,6 @@ __global__ void k_to_bf16(const float* __restrict__ p, long n, u16* __restrict__
   if (i < n) out[i] = f2bf(p[i]);
 }
 
-static inline unsigned blocks(long n, int t) { return (unsigned)((n + t - 1) / t); }
 
 // ------------------------------------------------------------------ network plan
 
@@ -578,14 +646,19 @@ long cnn_param_count() { return make_net(1, 32, 64, 64).nparam; }
 // Workspace for a batch: BF16 input and activations, FP32 pre-activations and
 // GEMM outputs, BF16 gradients, split-K partials, head buffers, BF16 weights.
 struct CnnWs {
-  size_t x, a[kCnnLayers], z[kCnnLayers], c, gz, ga, part, pbf, grad, head, total;
+  size_t x, a[kCnnLayers], z[kCnnLayers], c, gz, ga, part, pbf, grad, head, nrm, total;
 };
 
 static size_t al(size_t x) { return (x + 255) / 256 * 256; }
 constexpr int kWgradSplitsMax = 1024;
 
-// Split-K count of a weight gradient over P output positions (>= 256 positions per split).
-static int wgrad_splits(long P) { return (int)std::min<long>(kWgradSplitsMax, std::max<long>(1, P / 256)); }
+// Split-K count of a weight gradient (Co x K outputs) over P output positions:
+// about 2048 workgroups in all, at least 256 positions per split.
+static int wgrad_splits(long P, long Co, long K) {
+  const long tiles = ((Co + kBM - 1) / kBM) * ((K + kBN - 1) / kBN);
+  const long want = (2048 + tiles - 1) / tiles;
+  return (int)std::max<long>(1, std::min<long>({kWgradSplitsMax, P / 256, want}));
+}
 
 static CnnWs cnn_ws(const Net& net) {
   CnnWs w;
@@ -599,7 +672,8 @@ static CnnWs cnn_ws(const Net& net) {
     w.z[l] = take(L.P_out * L.Cout * sizeof(float));
     maxc = std::max(maxc, std::max(L.P_out * L.Cout, L.P_in * L.Cin));
     maxg = std::max(maxg, L.P_out * L.Cout);
-    maxpart = std::max(maxpart, (long)splits_used(L.P_out, wgrad_splits(L.P_out)) * L.Cout * 27 * L.Cin);
+    maxpart = std::max(maxpart, (long)splits_used(L.P_out, wgrad_splits(L.P_out, L.Cout, 27L * L.Cin)) * L.Cout * 27 * L.Cin);
+    maxpart = std::max(maxpart, (long)kBiasPartsMax * L.Cout);
   }
   w.c = take(maxc * sizeof(float));
   w.gz = take(maxg * sizeof(u16));
@@ -608,6 +682,7 @@ static CnnWs cnn_ws(const Net& net) {
   w.pbf = take(net.nparam * sizeof(u16));
   w.grad = take(net.nparam * sizeof(float));
   w.head = take((size_t)net.N * (kCnnOut * 3 + kCnnChannels[kCnnLayers] + 2) * sizeof(float));
+  w.nrm = take((size_t)net.N * kNormSlices * sizeof(double));
   w.total = b;
   return w;
 }
@@ -637,8 +712,12 @@ int cnn_run(const float* params, const float* x, int N, int Z, int Y, int X, con
   { ScopedTiming _tm("k_to_bf16", s);
   hipLaunchKernelGGL(k_to_bf16, dim3(blocks(net.nparam, 256)), dim3(256), 0, s, params, net.nparam, pbf);
   }
-  { ScopedTiming _tm("k_normalise", s);
-  hipLaunchKernelGGL(k_normalise, dim3(N), dim3(256), 0, s, x, (long)Z * Y * X, xb);
+  {
+    const long vol = (long)Z * Y * X;
+    double* nrm = (double*)(w + W.nrm);
+    ScopedTiming _tm("k_normalise", s);
+    hipLaunchKernelGGL(k_sumsq_slices, dim3(kNormSlices, N), dim3(256), 0, s, x, vol, nrm);
+    hipLaunchKernelGGL(k_scale_bf16, dim3(blocks(vol, 256), N), dim3(256), 0, s, x, vol, nrm, xb);
   }
   WO_HIP_CHECK(hipGetLastError());
   const u16* a_in = xb;
@@ -669,23 +748,23 @@ int cnn_run(const float* params, const float* x, int N, int Z, int Y, int X, con
     const Layer& L = net.L[l];
     const long K = 27L * L.Cin;
     const float* z = (const float*)(w + W.z[l]);
-    { ScopedTiming _tm("k_gelu_bwd", s);
-    hipLaunchKernelGGL(k_gelu_bwd, dim3(blocks(L.P_out * L.Cout, 256)), dim3(256), 0, s, ga, z,
-                       L.P_out * L.Cout, gz);
-    }
-    { ScopedTiming _tm("k_bias_grad", s);
-    hipLaunchKernelGGL(k_bias_grad, dim3(L.Cout), dim3(256), 0, s, gz, L.P_out, L.Cout,
-                       grad + L.b_off);
+    {
+      // gz and the bias gradient: partials in part, summed before the weight
+      // gradient reuses part
+      const long R = bias_rows(L.P_out, L.Cout);
+      const int G = (int)((L.P_out + R - 1) / R);
+      ScopedTiming _tm("k_gelu_bwd_bias", s);
+      hipLaunchKernelGGL(k_gelu_bwd_bias, dim3(G), dim3(256), 0, s, ga, z, L.P_out, L.Cout, R, gz, part);
+      WO_HIP_CHECK(reduce_parts(part, G, (long)L.Cout, grad + L.b_off, s));
     }
     const u16* a_prev = l == 0 ? xb : (const u16*)(w + W.a[l - 1]);
     // weight gradient, split over output positions
-    const int splits = wgrad_splits(L.P_out);
+    const int splits = wgrad_splits(L.P_out, L.Cout, K);
     const int zs = splits_used(L.P_out, splits);
     WO_HIP_CHECK(gemm(GatherT{gz, L.Cout}, GatherIm2colT{GatherIm2col{a_prev, L.g}}, part, L.Cout, K,
                       L.P_out, splits, s, "k_gemm_conv_wgrad"));
-    { ScopedTiming _tm("k_sum_splits", s);
-    hipLaunchKernelGGL(k_sum_splits, dim3(blocks((long)L.Cout * K, 256)), dim3(256), 0, s, part, zs,
-                       (long)L.Cout * K, grad + L.w_off);
+    { ScopedTiming _tm("k_reduce_parts", s);
+    WO_HIP_CHECK(reduce_parts(part, zs, (long)L.Cout * K, grad + L.w_off, s));
     }
     if (l > 0) {
       ConvGeom gd = L.g;
@@ -730,16 +809,14 @@ hipError_t conv_wgrad_raw(const u16* x, const u16* gz, int N, int D, int H, int 
   ConvGeom g{D, H, W, Cin, (D - 1) / 2 + 1, (H - 1) / 2 + 1, (W - 1) / 2 + 1};
   const long P = (long)N * g.Do * g.Ho * g.Wo;
   const long K = 27L * Cin;
-  int splits = wgrad_splits(P);
+  int splits = wgrad_splits(P, Cout, K);
   while (splits > 1 && (long)splits_used(P, splits) * Cout * K > part_elems) splits /= 2;
   const int zs = splits_used(P, splits);
   if ((long)zs * Cout * K > part_elems) return hipErrorInvalidValue;
   hipError_t e = gemm(GatherT{gz, Cout}, GatherIm2colT{GatherIm2col{x, g}}, part, Cout, K, P, splits,
                       s, "k_gemm_conv_wgrad");
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_sum_splits, dim3(blocks((long)Cout * K, 256)), dim3(256), 0, s, part, zs,
-                     (long)Cout * K, out);
-  return hipGetLastError();
+  return reduce_parts(part, zs, (long)Cout * K, out, s);
 }
 
 }  // namespace wo
