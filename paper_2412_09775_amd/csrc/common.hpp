@@ -219,6 +219,29 @@ __device__ __forceinline__ void gather_to_lds_map(float2* buf, int total, int ti
   }
 }
 
+// Two-phase gather: load(e) only issues the global loads of element e and
+// returns them raw; finish(e, raw) turns them into the LDS value after every
+// load of the thread has been issued.  Data-dependent branches or uses of a
+// loaded value inside load() would make the compiler wait for each load in
+// turn; keep them in finish().
+template <typename L, typename F, typename S, typename G>
+__device__ __forceinline__ void gather2_to_lds(float2* buf, int total, int tid, int nthr, L load,
+                                               F finish, S slot, G mid) {
+  using T = decltype(load(0));
+  T t[kEmax];
+#pragma unroll
+  for (int i = 0; i < kEmax; ++i) {
+    const int e = tid + i * nthr;
+    if (e < total) t[i] = load(e);
+  }
+  mid();
+#pragma unroll
+  for (int i = 0; i < kEmax; ++i) {
+    const int e = tid + i * nthr;
+    if (e < total) buf[slot(e)] = finish(e, t[i]);
+  }
+}
+
 // As scatter_from_lds, element e read from buf[slot(e)].
 template <typename F, typename S>
 __device__ __forceinline__ void scatter_from_lds_map(const float2* buf, int total, int tid, int nthr,
@@ -282,6 +305,16 @@ __host__ __device__ inline int pow2_shift(int n) {
   return s;
 }
 
+// Twiddles w^r (r < R) of one butterfly from w = w1: products of lower powers
+// (at most three deep), so a butterfly reads one table entry instead of R - 1.
+template <int R>
+__device__ __forceinline__ void twiddle_powers(float2 (&w)[R], float2 w1) {
+  w[0] = make_float2(1.f, 0.f);
+  if constexpr (R > 1) w[1] = w1;
+#pragma unroll
+  for (int r = 2; r < R; ++r) w[r] = cmul(w[r / 2], w[r - r / 2]);
+}
+
 template <int R>
 __device__ __forceinline__ void stockham_pass(float2* lds, const LdsLines L, int n, int ns,
                                               const float2* tw, float s, int tid, int nthr) {
@@ -305,15 +338,17 @@ __device__ __forceinline__ void stockham_pass(float2* lds, const LdsLines L, int
       const int km = k % ns;
       base[b] = lb;
       kk[b] = k;
+      float2 w[R];
+      if (ns > 1) {
+        float2 w1 = tw[km * twstep];
+        if (s > 0.f) w1.y = -w1.y;
+        twiddle_powers<R>(w, w1);
+      }
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         const int idx = k + r * nb;
         float2 x = lds[lb + (L.pad ? row_slot(idx) : idx * L.es)];
-        if (r > 0) {
-          float2 w = tw[r * km * twstep];
-          if (s > 0.f) w.y = -w.y;
-          x = cmul(x, w);
-        }
+        if (r > 0 && ns > 1) x = cmul(x, w[r]);
         v[b][r] = x;
       }
       dft_small<R>(v[b], s);
@@ -518,14 +553,18 @@ __device__ __forceinline__ void static_pass(float2* lds, int nl_rt, int es, int 
       const int km = k % NS;
       base[b] = lb;
       kk[b] = k;
+      float2 w[R];
+      if constexpr (NS > 1) {
+        float2 w1 = tw[km * TWS];
+        if (s > 0.f) w1.y = -w1.y;
+        twiddle_powers<R>(w, w1);
+      }
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         const int idx = k + r * NB;
         float2 x = lds[lb + (PD ? row_slot(idx) : idx * es)];
-        if (r > 0) {
-          float2 w = tw[r * km * TWS];
-          if (s > 0.f) w.y = -w.y;
-          x = cmul(x, w);
+        if constexpr (NS > 1) {
+          if (r > 0) x = cmul(x, w[r]);
         }
         v[b][r] = x;
       }

@@ -37,11 +37,15 @@ __global__ __launch_bounds__(1024) void k_rows_r2c(const float* __restrict__ in,
   __syncthreads();
   const int Xc = NS > 0 ? NS : X;   // compile-time length for the index arithmetic
   const int LS = row_stride(Xc);    // padded line pitch in LDS
-  gather_to_lds_map(buf, nl * Xc, tid, nthr, [&](int e) {
+  // a missing second row (odd row count) loads the first row again and is
+  // zeroed after the loads
+  gather2_to_lds(buf, nl * Xc, tid, nthr, [&](int e) {
     const int l = e / Xc, i = e - l * Xc;
-    const float a = in[rin[2 * l] * X + i];
-    const float b = rin[2 * l + 1] >= 0 ? in[rin[2 * l + 1] * X + i] : 0.f;
-    return make_float2(a, b);
+    const long ra = rin[2 * l], rb = rin[2 * l + 1];
+    return make_float2(in[ra * X + i], in[(rb >= 0 ? rb : ra) * X + i]);
+  }, [&](int e, float2 v) {
+    const int l = e / Xc;
+    return make_float2(v.x, rin[2 * l + 1] >= 0 ? v.y : 0.f);
   }, [&](int e) {
     const int l = e / Xc;
     return l * LS + row_slot(e - l * Xc);
@@ -91,12 +95,19 @@ __global__ __launch_bounds__(1024) void k_rows_c2r(const float2* __restrict__ in
     const int l = e / Xc;
     return l * LS + row_slot(e - l * Xc);
   };
-  gather_to_lds_map(buf, nl * Xc, tid, nthr, [&](int e) {
+  gather2_to_lds(buf, nl * Xc, tid, nthr, [&](int e) {
+    const int l = e / Xc, k = e - l * Xc;
+    const int kk = 2 * k > Xc ? Xc - k : k;
+    const long ra = rin[2 * l], rb = rin[2 * l + 1];
+    const float2 A = in[ra * Xh + kk];
+    const float2 B = in[(rb >= 0 ? rb : ra) * Xh + kk];
+    return make_float4(A.x, A.y, B.x, B.y);
+  }, [&](int e, float4 v) {
     const int l = e / Xc, k = e - l * Xc;
     const bool mirror = 2 * k > Xc;
     const int kk = mirror ? Xc - k : k;
-    float2 A = in[rin[2 * l] * Xh + kk];
-    float2 B = rin[2 * l + 1] >= 0 ? in[rin[2 * l + 1] * Xh + kk] : make_float2(0.f, 0.f);
+    float2 A = make_float2(v.x, v.y), B = make_float2(v.z, v.w);
+    if (rin[2 * l + 1] < 0) B = make_float2(0.f, 0.f);
     if (kk == 0 || 2 * kk == Xc) { A.y = 0.f; B.y = 0.f; }   // Re of the inverse ignores them
     if (mirror) { A.y = -A.y; B.y = -B.y; }
     return make_float2(A.x - B.y, A.y + B.x);
