@@ -31,7 +31,9 @@
  *    extension H(-nu) = conj(H(nu)) (transfer functions of real data are
  *    Hermitian, Methods "Summary of transfer functions").
  *  * Sizes nz, ny, nx must factor into 2, 3 and 5 and lie in [1, 4096] (ny, nx
- *    even); otherwise WO_EUNSUPPORTED.
+ *    even); otherwise WO_EUNSUPPORTED.  wo_forward, wo_reconstruct and
+ *    wo_adjoint of a 3D model also need max(C, P) * nz <= 8192 (one Z line of
+ *    every channel and property in one workgroup), else WO_EUNSUPPORTED.
  *  * Units: lengths in micrometres, angles in radians.  Label-free properties
  *    are radians per voxel (phase 2 pi dn dz / lambda0, absorption
  *    2 pi dkappa dz / lambda0); label-free data are the relative contrast

@@ -984,6 +984,7 @@ int wo_forward(const wo_optics* o, int32_t n, const void* tf, const float* f, co
   Shape s;
   bank_shape(o, &s);
   if (s.P != 1 && s.P != 2 && s.P != 4) return WO_EUNSUPPORTED;
+  if (!s.thin && !zop_fits((int)s.Z, std::max(s.C, s.P))) return WO_EUNSUPPORTED;
   if (ws_bytes < linear_ws(n, s)) return WO_ENOMEM;
   return run_linear(o, n, s, (const float2*)tf, f, d_out, b, kModeForward, 0.f, ws,
                     (hipStream_t)stream);
@@ -1001,6 +1002,7 @@ int wo_reconstruct(const wo_optics* o, int32_t n, const void* tf, const float* d
   Shape s;
   bank_shape(o, &s);
   if (s.P != 1 && s.P != 2 && s.P != 4) return WO_EUNSUPPORTED;
+  if (!s.thin && !zop_fits((int)s.Z, std::max(s.C, s.P))) return WO_EUNSUPPORTED;
   if (eta == 0.0 && s.P != 1) return WO_EUNSUPPORTED;
   if (ws_bytes < linear_ws(n, s)) return WO_ENOMEM;
   return run_linear(o, n, s, (const float2*)tf, d, f_out, b, kModeSolve, (float)eta, ws,
@@ -1018,6 +1020,7 @@ int wo_adjoint(const wo_optics* o, int32_t n, const void* tf, const float* r, fl
   Shape s;
   bank_shape(o, &s);
   if (s.P != 1 && s.P != 2 && s.P != 4) return WO_EUNSUPPORTED;
+  if (!s.thin && !zop_fits((int)s.Z, std::max(s.C, s.P))) return WO_EUNSUPPORTED;
   if (ws_bytes < linear_ws(n, s)) return WO_ENOMEM;
   return run_linear(o, n, s, (const float2*)tf, r, g_out, nullptr, kModeAdjoint, 0.f, ws,
                     (hipStream_t)stream);

@@ -583,6 +583,8 @@ static FftChoice zop_default(int Z, int CH) {
   return FftChoice{W, threads_for((long)CH * Z * W), 0};
 }
 
+bool zop_fits(int Z, int CH) { return zop_choice_ok(Z, CH, zop_default(Z, CH)); }
+
 hipError_t launch_zop(float2* spec, const float2* tf, int C, int P, int Z, long M, int slots,
                       int npatch, int mode, float eta, const float* bg, float inv_n, double n_full,
                       hipStream_t s) {

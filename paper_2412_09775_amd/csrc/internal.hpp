@@ -102,6 +102,8 @@ hipError_t launch_cols(float2* data, int N, long M, long planes_per_group, long 
 
 enum SpectralMode { kModeForward = 0, kModeSolve = 1, kModeAdjoint = 2 };
 
+// Whether one Z line of CH channels fits a workgroup of the fused Z pass.
+bool zop_fits(int Z, int CH);
 // 3D: forward Z-FFT, per-frequency op, inverse Z-FFT, fused.  spec holds
 // `slots` channel slots of [Z][M] per patch; tf holds [C][P][Z][M] per patch.
 hipError_t launch_zop(float2* spec, const float2* tf, int C, int P, int Z, long M, int slots,

@@ -88,6 +88,10 @@ def test_null_and_small_workspace_are_rejected(lib):
     assert lib.wo_tune_workspace_size(arr, 0, 1) == 0
     big = api.optics_array(_optics(nx=8192))        # beyond the 4096 limit
     assert lib.wo_transfer_function(big, 1, ctypes.c_void_p(1), ctypes.c_void_p(1), 1 << 40, None) == -2
+    # one Z line of both properties must fit a workgroup of the fused Z pass
+    deep = api.optics_array(_optics(model=api.MODEL_POL5_3D, nz=2048))   # 5 x 2048 > 8192
+    assert lib.wo_reconstruct(deep, 1, ctypes.c_void_p(1), ctypes.c_void_p(1), None, 1e-3,
+                              ctypes.c_void_p(1), ctypes.c_void_p(1), 1 << 40, None) == -2
     mixed = api.optics_array([_optics(), _optics(nz=16)])
     assert lib.wo_forward(mixed, 2, ctypes.c_void_p(1), ctypes.c_void_p(1), None,
                           ctypes.c_void_p(1), ctypes.c_void_p(1), 1 << 40, None) == -1
