@@ -253,8 +253,10 @@ int wo_stitch_tiles(const float* tiles, int32_t ny_t, int32_t nx_t, int32_t P, i
 /* ---------------------------------------------------------------- FFT schedule tuner
  * Not in the paper (its transforms are library calls).  Every FFT pass of the
  * library -- rows along X (real <-> half spectrum), strided columns along Y
- * (and Z for the transfer functions), and the Z pass fused with the
- * per-frequency operator -- is launched with a schedule: the lines or columns
+ * (and Z for the transfer functions), the Z pass fused with the
+ * per-frequency operator, and the row pass of the label-free transfer
+ * functions (inverse X transforms of both fields, their product, forward X
+ * transform) -- is launched with a schedule: the lines, rows or columns
  * one workgroup transforms, the workgroup size, and the radix plan (compiled
  * stages for the compiled lengths, else a runtime plan in one of three radix
  * orders).  Without tuning each pass takes a fixed heuristic schedule; a
@@ -274,7 +276,7 @@ int wo_stitch_tiles(const float* tiles, int32_t ny_t, int32_t nx_t, int32_t P, i
 int wo_fft_tune(int32_t op, const wo_optics* o, int32_t n, const void* tf, const float* in, float* out,
                 double eta, int32_t reps, void* ws, size_t ws_bytes, void* stream);
 /* The table as text, one line "kind n m batch extra w threads plan" per entry
- * (kind: rows_r2c, rows_c2r, cols, zop); NUL-terminated, truncated to len;
+ * (kind: rows_r2c, rows_c2r, cols, zop, tf_rows); NUL-terminated, truncated to len;
  * *needed (may be NULL) receives the full size including the NUL. */
 int wo_fft_plans_export(char* buf, size_t len, size_t* needed);
 /* Adds entries in the export format; all or none: WO_EINVAL if a line is

@@ -157,16 +157,12 @@ __global__ __launch_bounds__(1024) void k_tf_rows_bwd(const double* __restrict__
   float2* a_src = ab + (v * 2 + 0) * rpp * X;
   float2* b_src = ab + (v * 2 + 1) * rpp * X;
   const float2* g_src = g + v * rpp * 2 * Xh;
-  if (tid == 0) {
-    double t = 0.0;
-    for (long i = 0; i < tiles_x; ++i) t += partials[v * tiles_x + i];
-    ibg_s = t;
-  }
+  const int PS = pad_shift(X);   // row padding
   const int LS = row_stride(X);      // padded line pitch in LDS
   // lines 2r, 2r + 1: a (then u_A), b (then u_B) of row r; line 2 nr + r: Gamma of row r
   auto slot = [&](int e) {
     const int t = e / X;
-    return t * LS + row_slot(e - t * X);
+    return t * LS + row_slot(e - t * X, PS);
   };
   gather_to_lds_map(buf, nr * 3 * X, tid, nthr, [&](int e) {
     const int i = e % X;
@@ -186,7 +182,7 @@ __global__ __launch_bounds__(1024) void k_tf_rows_bwd(const double* __restrict__
     if (kk == 0 || 2 * kk == X) { P.y = 0.f; A.y = 0.f; }   // Re of the inverse ignores them
     if (mirror) { P.y = -P.y; A.y = -A.y; }
     return make_float2(P.x - A.y, P.y + A.x);
-  }, slot, [] {});
+  }, slot, [&] { wave0_sum(partials + v * tiles_x, tiles_x, &ibg_s); });   // sum S P^2
   __syncthreads();
   fft_lines<NS, 0, false, kEmax, true>(buf, LdsLines{3 * nr, 1, LS, false, -1, true}, plan, tw, 1.f,
                                        tid, nthr);
@@ -194,7 +190,7 @@ __global__ __launch_bounds__(1024) void k_tf_rows_bwd(const double* __restrict__
   double dsum = 0.0;
   for (int e = tid; e < nr * X; e += nthr) {
     const int r = e / X, i = e - r * X;
-    const int si = row_slot(i);
+    const int si = row_slot(i, PS);
     const float2 G = buf[(2 * nr + r) * LS + si];   // (Gamma_phase, Gamma_abs)
     const float2 a = buf[2 * r * LS + si], b = buf[(2 * r + 1) * LS + si];
     const float2 gb = cmul(G, b);

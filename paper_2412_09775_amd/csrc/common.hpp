@@ -286,16 +286,22 @@ struct LdsLines {
   int ls;     // line stride
   bool linefast;
   int shift = -1;   // log2(nl) when nl is a power of two (slot -> line by masks), else -1
-  bool pad = false; // row layout with one padding slot after every 8 elements (see row_slot)
+  bool pad = false; // padded row layout (see row_slot)
 };
 
-// Row layout (lines contiguous in LDS): element i of a line sits at
-// row_slot(i) = i + i / 8.  A Stockham pass writes its first outputs with a
-// stride of R elements; the padding turns that stride into R + R/8, which
-// spreads the 64 lanes of a write over the LDS banks.  row_stride(n) is the
-// line pitch that holds n padded elements.
-__host__ __device__ __forceinline__ int row_slot(int i) { return i + (i >> 3); }
-__host__ __device__ __forceinline__ int row_stride(int n) { return n + (n >> 3) + 1; }
+// Row layout (lines contiguous in LDS): element i of a line of length n sits
+// at row_slot(i, pad_shift(n)) = i + (i >> pad_shift(n)), one padding slot per
+// 8 or 16 elements.  LDS serves a 64-bit access 16 lanes at a time over 32
+// four-byte banks.  A Stockham pass writes its first outputs with a stride of
+// R elements (16 R bytes, every lane of a group on the same banks); the
+// padding staggers them.  One slot per 16 elements keeps 16 consecutive
+// elements (a unit-stride access) on 32 distinct banks; one per 8 splits such
+// groups but suits short rows (measured: 512-point rows run about 3 % faster
+// with 16, the 128-point backward rows of the auto-tune 7 % faster with 8).
+// row_stride(n) is the line pitch that holds n padded elements.
+__host__ __device__ constexpr int pad_shift(int n) { return n <= 128 ? 3 : 4; }
+__host__ __device__ __forceinline__ int row_slot(int i, int ps) { return i + (i >> ps); }
+__host__ __device__ __forceinline__ int row_stride(int n) { return n + (n >> pad_shift(n)) + 1; }
 
 // log2(n) for a power of two n, else -1.
 __host__ __device__ inline int pow2_shift(int n) {
@@ -347,7 +353,7 @@ __device__ __forceinline__ void stockham_pass(float2* lds, const LdsLines L, int
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         const int idx = k + r * nb;
-        float2 x = lds[lb + (L.pad ? row_slot(idx) : idx * L.es)];
+        float2 x = lds[lb + (L.pad ? row_slot(idx, pad_shift(n)) : idx * L.es)];
         if (r > 0 && ns > 1) x = cmul(x, w[r]);
         v[b][r] = x;
       }
@@ -363,7 +369,7 @@ __device__ __forceinline__ void stockham_pass(float2* lds, const LdsLines L, int
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         const int idx = d0 + r * ns;
-        lds[base[b] + (L.pad ? row_slot(idx) : idx * L.es)] = v[b][r];
+        lds[base[b] + (L.pad ? row_slot(idx, pad_shift(n)) : idx * L.es)] = v[b][r];
       }
     }
   }
@@ -399,6 +405,18 @@ __device__ __forceinline__ long xcd_block() {
   const unsigned q = n / kXcds, r = n % kXcds;
   const unsigned x = b % kXcds, k = b / kXcds;
   return (long)(x < r ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k);
+}
+
+// Sum of p[0..n) by wave 0 of the workgroup in a fixed order (lane-strided
+// sums, then a shuffle tree); lane 0 stores it to *out, other waves return at
+// once.  Called between issuing a tile's loads and storing them to LDS, its
+// loads overlap theirs.  The caller synchronises before reading *out.
+__device__ __forceinline__ void wave0_sum(const double* p, long n, double* out) {
+  if (threadIdx.x >= 64) return;
+  double v = 0.0;
+  for (long i = threadIdx.x; i < n; i += 64) v += p[i];
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  if (threadIdx.x == 0) *out = v;
 }
 
 // ---------------------------------------------------------------- optics
@@ -562,7 +580,7 @@ __device__ __forceinline__ void static_pass(float2* lds, int nl_rt, int es, int 
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         const int idx = k + r * NB;
-        float2 x = lds[lb + (PD ? row_slot(idx) : idx * es)];
+        float2 x = lds[lb + (PD ? row_slot(idx, pad_shift(N)) : idx * es)];
         if constexpr (NS > 1) {
           if (r > 0) x = cmul(x, w[r]);
         }
@@ -580,7 +598,7 @@ __device__ __forceinline__ void static_pass(float2* lds, int nl_rt, int es, int 
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         const int idx = d0 + r * NS;
-        lds[base[b] + (PD ? row_slot(idx) : idx * es)] = v[b][r];
+        lds[base[b] + (PD ? row_slot(idx, pad_shift(N)) : idx * es)] = v[b][r];
       }
     }
   }

@@ -36,6 +36,7 @@ __global__ __launch_bounds__(1024) void k_rows_r2c(const float* __restrict__ in,
   }
   __syncthreads();
   const int Xc = NS > 0 ? NS : X;   // compile-time length for the index arithmetic
+  const int PS = pad_shift(Xc);   // row padding
   const int LS = row_stride(Xc);    // padded line pitch in LDS
   // a missing second row (odd row count) loads the first row again and is
   // zeroed after the loads
@@ -48,7 +49,7 @@ __global__ __launch_bounds__(1024) void k_rows_r2c(const float* __restrict__ in,
     return make_float2(v.x, rin[2 * l + 1] >= 0 ? v.y : 0.f);
   }, [&](int e) {
     const int l = e / Xc;
-    return l * LS + row_slot(e - l * Xc);
+    return l * LS + row_slot(e - l * Xc, PS);
   }, [&] { fill_twiddles(tw, X, tid, nthr); });
   __syncthreads();
   fft_lines<NS, 0, false, kEmax, true>(buf, LdsLines{nl, 1, LS, false, -1, true}, plan, tw, -1.f, tid,
@@ -59,8 +60,8 @@ __global__ __launch_bounds__(1024) void k_rows_r2c(const float* __restrict__ in,
     const int e = tid + i * nthr;
     if (e < nl * Xh) {
       const int l = e / Xh, k = e - l * Xh;
-      const float2 zk = buf[l * LS + row_slot(k)];
-      const float2 zm = buf[l * LS + row_slot(k == 0 ? 0 : Xc - k)];
+      const float2 zk = buf[l * LS + row_slot(k, PS)];
+      const float2 zm = buf[l * LS + row_slot(k == 0 ? 0 : Xc - k, PS)];
       const float2 A = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y));
       const float2 B = make_float2(0.5f * (zk.y + zm.y), -0.5f * (zk.x - zm.x));
       out[rout[2 * l] * Xh + k] = A;
@@ -90,10 +91,11 @@ __global__ __launch_bounds__(1024) void k_rows_c2r(const float2* __restrict__ in
   __syncthreads();
   const int Xc = NS > 0 ? NS : X;   // compile-time length for the index arithmetic
   const int Xh = Xc / 2 + 1;
+  const int PS = pad_shift(Xc);   // row padding
   const int LS = row_stride(Xc);    // padded line pitch in LDS
   auto slot = [&](int e) {
     const int l = e / Xc;
-    return l * LS + row_slot(e - l * Xc);
+    return l * LS + row_slot(e - l * Xc, PS);
   };
   gather2_to_lds(buf, nl * Xc, tid, nthr, [&](int e) {
     const int l = e / Xc, k = e - l * Xc;
@@ -142,9 +144,6 @@ static bool compiled_length(int n) {
   }
 }
 
-static bool threads_ok(int thr, long elems) {
-  return thr >= 64 && thr <= kMaxThreads && thr % 64 == 0 && (long)thr * kEmax >= elems;
-}
 
 static bool rows_choice_ok(int X, const FftChoice& c) {
   const long elems = (long)c.w * X;
@@ -680,6 +679,15 @@ std::vector<FftChoice> fft_candidates(const FftKey& k) {
         for (int t : thread_options((long)w * k.n)) {
           const FftChoice c{w, t, pl};
           if (cols_choice_ok(k.n, c)) add(c);
+        }
+  } else if (k.kind == kFftTfRows) {
+    const FftChoice d = tf_rows_default(k.n);
+    add(d);
+    for (int pl : plans)
+      for (int w : {1, 2, 3, 4, 6, 8, 12, 16, 24, 32})
+        for (int t : thread_options(2L * w * k.n)) {
+          const FftChoice c{w, t, pl};
+          if (tf_rows_choice_ok(k.n, c)) add(c);
         }
   } else if (k.kind == kFftZop) {
     const int P = k.extra / 1000, C = (k.extra / 10) % 100, mode = k.extra % 10;

@@ -46,7 +46,8 @@ struct ScopedTiming {
 //
 // Launch schedule of one FFT pass for one problem shape, chosen by timing
 // (wo_fft_tune) or by the default heuristics when the table has no entry.
-enum FftKind { kFftRowsR2C = 0, kFftRowsC2R = 1, kFftCols = 2, kFftZop = 3 };
+enum FftKind { kFftRowsR2C = 0, kFftRowsC2R = 1, kFftCols = 2, kFftZop = 3, kFftTfRows = 4 };
+constexpr int kFftKinds = 5;
 // plan: 0 = the compiled stages of the length when there are some, else the
 // runtime plan in the default radix order; 1 = runtime plan, default order
 // (8, 4, 2, 3, 5); 2 = runtime plan, reversed pass order; 3 = runtime plan,
@@ -75,6 +76,14 @@ void fft_store(const FftKey& k, const FftChoice& c);
 // Changes whenever the table changes (graphs captured before are stale).
 unsigned long long fft_table_version();
 // Every schedule the launcher of k accepts (the first is the default).
+// Schedules of the label-free transfer-function row pass (w = rows per
+// workgroup, two LDS lines each).
+bool tf_rows_choice_ok(int X, const FftChoice& c);
+FftChoice tf_rows_default(int X);
+// A workgroup of `thr` threads can own `elems` elements (kEmax per thread).
+inline bool threads_ok(int thr, long elems) {
+  return thr >= 64 && thr <= kMaxThreads && thr % 64 == 0 && (long)thr * kEmax >= elems;
+}
 std::vector<FftChoice> fft_candidates(const FftKey& k);
 // While a tuning run records, each tunable launch registers its key and a
 // closure that repeats it.

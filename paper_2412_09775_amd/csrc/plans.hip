@@ -30,12 +30,13 @@ const char* kind_name(int k) {
     case kFftRowsC2R: return "rows_c2r";
     case kFftCols: return "cols";
     case kFftZop: return "zop";
+    case kFftTfRows: return "tf_rows";
     default: return "?";
   }
 }
 
 int kind_of(const char* s) {
-  for (int k = 0; k < 4; ++k)
+  for (int k = 0; k < kFftKinds; ++k)
     if (strcmp(s, kind_name(k)) == 0) return k;
   return -1;
 }

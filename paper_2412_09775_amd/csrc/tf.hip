@@ -202,11 +202,16 @@ int tf_z_chunk(const Sampling& sm, long tiles_x, long npatch, long target) {
   return (int)zc;
 }
 
+// Column-tile width of the field kernel: at most 4096 elements (512 threads)
+// per workgroup.  The kernel synchronises its workgroup several times per
+// plane, so several smaller workgroups per CU hide those waits better than
+// one large one (measured: 96x512x512, 8 columns x 2 fields 169 us, 4 columns
+// 135 us).
 int tf_tile_width(const Sampling& sm) {
   const int nf = sm.model == kFluor3D ? 1 : 2;
   const long lim = lds_limit_bytes() / (long)sizeof(float2);
   int W = 16;
-  while (W > 1 && ((long)W * nf * sm.ny > kMaxElems || sm.ny + (long)W * nf * sm.ny > lim)) W /= 2;
+  while (W > 1 && ((long)W * nf * sm.ny > 4096 || sm.ny + (long)W * nf * sm.ny > lim)) W /= 2;
   return W;
 }
 
@@ -250,11 +255,6 @@ hipError_t launch_tf_fields_y(const DevOptics* opt, const Sampling& sm, int npat
 
 // out[patch * patch_stride + p * pstride + z * zstride + y * Xh + k], p = 0 phase, 1 absorption
 // (pstride < 0: phase only)
-__device__ __forceinline__ double pupil_total(const double* partials, long tiles_x) {
-  double t = 0.0;
-  for (long i = 0; i < tiles_x; ++i) t += partials[i];
-  return t;
-}
 
 template <int NS>
 __global__ __launch_bounds__(1024) void k_tf_rows_lf(const double* __restrict__ partials,
@@ -279,7 +279,7 @@ __global__ __launch_bounds__(1024) void k_tf_rows_lf(const double* __restrict__ 
   const int z0 = (int)(row0 / Y), y0 = (int)(row0 - (long)z0 * Y);
   const float2* a_src = ab + (patch * 2 + 0) * rpp * X;
   const float2* b_src = ab + (patch * 2 + 1) * rpp * X;
-  if (tid == 0) ibg_s = pupil_total(partials + patch * tiles_x, tiles_x);
+  const int PS = pad_shift(X);   // row padding
   const int LS = row_stride(X);      // padded line pitch in LDS
   // line 2r holds a, line 2r + 1 holds b of row r
   gather_to_lds_map(buf, nr * 2 * X, tid, nthr, [&](int e) {
@@ -290,14 +290,14 @@ __global__ __launch_bounds__(1024) void k_tf_rows_lf(const double* __restrict__ 
     return src[(row0 + r) * X + i];
   }, [&](int e) {
     const int t = e / X;
-    return t * LS + row_slot(e - t * X);
-  }, [] {});
+    return t * LS + row_slot(e - t * X, PS);
+  }, [&] { wave0_sum(partials + patch * tiles_x, tiles_x, &ibg_s); });   // sum S P^2
   __syncthreads();
   fft_lines<NS, 0, false, kEmax, true>(buf, LdsLines{2 * nr, 1, LS, false, -1, true}, plan, tw, 1.f,
                                        tid, nthr);
   const float cs = (float)(1.0 / ((double)X * (double)Y * ibg_s));
   for (int e = tid; e < nr * X; e += nthr) {
-    const int r = e / X, i = row_slot(e - r * X);
+    const int r = e / X, i = row_slot(e - r * X, PS);
     const float2 a = buf[2 * r * LS + i], b = buf[(2 * r + 1) * LS + i];
     buf[2 * r * LS + i] = cscale(cmulconj(b, a), cs);
   }
@@ -307,8 +307,8 @@ __global__ __launch_bounds__(1024) void k_tf_rows_lf(const double* __restrict__ 
   float2* op = out + patch * patch_stride;
   for (int e = tid; e < nr * Xh; e += nthr) {
     const int r = e / Xh, k = e - r * Xh;
-    const float2 Ck = buf[2 * r * LS + row_slot(k)];
-    const float2 Cm = buf[2 * r * LS + row_slot(k == 0 ? 0 : X - k)];
+    const float2 Ck = buf[2 * r * LS + row_slot(k, PS)];
+    const float2 Cm = buf[2 * r * LS + row_slot(k == 0 ? 0 : X - k, PS)];
     int y = y0 + r, z = z0;
     while (y >= Y) { y -= Y; ++z; }
     const float2 U = make_float2(Ck.x + Cm.x, Ck.y - Cm.y);          // C + conj(C(-k))
@@ -318,19 +318,40 @@ __global__ __launch_bounds__(1024) void k_tf_rows_lf(const double* __restrict__ 
   }
 }
 
+bool tf_rows_choice_ok(int X, const FftChoice& c) {
+  const long elems = 2L * c.w * X;
+  return c.w >= 1 && c.w <= 64 && elems <= kMaxElems && threads_ok(c.threads, elems) &&
+         (long)(X + 2L * c.w * row_stride(X)) * (long)sizeof(float2) <= lds_limit_bytes() &&
+         c.plan >= 0 && c.plan <= 3;
+}
+
+FftChoice tf_rows_default(int X) {
+  int R = 2048 / X;                       // rows per workgroup (2 lines each)
+  if (R < 1) R = 1;
+  while (R > 1 && (2L * R * X > kMaxElems ||
+                   (long)(X + 2L * R * row_stride(X)) * (long)sizeof(float2) > lds_limit_bytes()))
+    --R;
+  return FftChoice{R, threads_for(2L * R * X), 0};
+}
+
 hipError_t launch_tf_rows_labelfree(const double* partials, const Sampling& sm, int npatch,
                                     const float2* ab, float2* out, long patch_stride,
                                     long pstride, long zstride, hipStream_t s) {
+  const FftKey key{kFftTfRows, sm.nx, sm.ny, (long)npatch * sm.nz, pstride < 0 ? 1 : 0};
+  if (fft_recording())
+    fft_record(key, [=] {
+      return launch_tf_rows_labelfree(partials, sm, npatch, ab, out, patch_stride, pstride, zstride, s);
+    });
+  FftChoice c;
+  if (!fft_lookup(key, &c) || !tf_rows_choice_ok(sm.nx, c)) c = tf_rows_default(sm.nx);
   const long tiles_x = (sm.nx + tf_tile_width(sm) - 1) / tf_tile_width(sm);
   FftPlan plan;
-  if (!make_plan(sm.nx, &plan)) return hipErrorInvalidValue;
-  int R = 2048 / sm.nx;                       // rows per workgroup (2 lines each)
-  if (R < 1) R = 1;
-  while (R > 1 && 2L * R * sm.nx > kMaxElems) --R;
+  if (!make_plan_variant(sm.nx, c.plan, &plan)) return hipErrorInvalidValue;
+  const int R = c.w;
   const long rpp = (long)sm.nz * sm.ny;
   const long wpp = (rpp + R - 1) / R;
   const long nwg = wpp * npatch;
-  const int thr = threads_for(2L * R * sm.nx);
+  const int thr = c.threads;
   const size_t lds = (size_t)(sm.nx + 2L * R * row_stride(sm.nx)) * sizeof(float2);
   ScopedTiming _t("k_tf_rows_lf", s);
 #define X_(NN)                                                                                   \
@@ -338,11 +359,11 @@ hipError_t launch_tf_rows_labelfree(const double* partials, const Sampling& sm, 
     hipLaunchKernelGGL((k_tf_rows_lf<NN>), dim3((unsigned)nwg), dim3(thr), lds, s, partials, tiles_x, \
                        sm, ab, out, patch_stride, pstride, zstride, R, wpp, plan);               \
     return hipGetLastError();
-  switch (sm.nx) {
-    WO_LATERAL_SIZES(X_)
-    default:
-      break;
-  }
+  if (c.plan == 0) switch (sm.nx) {
+      WO_LATERAL_SIZES(X_)
+      default:
+        break;
+    }
 #undef X_
   hipLaunchKernelGGL((k_tf_rows_lf<0>), dim3((unsigned)nwg), dim3(thr), lds, s, partials, tiles_x, sm,
                      ab, out, patch_stride, pstride, zstride, R, wpp, plan);
@@ -371,11 +392,10 @@ __global__ __launch_bounds__(1024) void k_tf_rows_fl(const double* __restrict__ 
   const int nrows = (int)min(2L * pairs_per_wg, rpp - row0);
   const int np = (nrows + 1) / 2;
   const float2* src = h + patch * rpp * X;
-  if (tid == 0) ibg_s = pupil_total(partials + patch * tiles_x, tiles_x);
   gather_to_lds(buf, 2 * np * X, tid, nthr, [&](int e) {
     const int l = e / X, i = e - l * X;
     return l < nrows ? src[(row0 + l) * X + i] : make_float2(0.f, 0.f);
-  });
+  }, [&] { wave0_sum(partials + patch * tiles_x, tiles_x, &ibg_s); });   // sum P^2
   __syncthreads();
   fft_lines<NS, 0, false>(buf, LdsLines{2 * np, 1, X, false}, plan, tw, 1.f, tid, nthr);
   const double norm = 1.0 / ((double)Z * (double)X * (double)Y * ibg_s);
