@@ -184,10 +184,10 @@ __global__ __launch_bounds__(1024) void k_tf_rows_bwd(const double* __restrict__
     return make_float2(P.x - A.y, P.y + A.x);
   }, slot, [&] { wave0_sum(partials + v * tiles_x, tiles_x, &ibg_s); });   // sum S P^2
   __syncthreads();
-  fft_lines<NS, 0, false, kEmax, true>(buf, LdsLines{3 * nr, 1, LS, false, -1, true}, plan, tw, 1.f,
-                                       tid, nthr);
   const float k = (float)(1.0 / ((double)X * (double)Y * ibg_s));
   double dsum = 0.0;
+  fft_lines<NS, 0, false, kEmax, true>(buf, LdsLines{3 * nr, 1, LS, false, -1, true}, plan, tw, 1.f,
+                                       tid, nthr);
   for (int e = tid; e < nr * X; e += nthr) {
     const int r = e / X, i = e - r * X;
     const int si = row_slot(i, PS);

@@ -615,6 +615,113 @@ __device__ __forceinline__ void static_fft(float2* lds, int nl_rt, int es, int l
   }
 }
 
+// Radix order of the compiled stages, forward (REV false) or reversed.  Any
+// order is a valid Stockham sequence (the span of a pass is the product of the
+// radices before it); a transform in reversed order ends with a pass whose
+// outputs, k + r N/R0, are the inputs of the first pass (radix R0, span 1) of
+// a transform in forward order, so the two can meet in registers.
+template <int N, bool REV>
+struct OrderedPlan {
+  static constexpr int passes() { return StaticPlan<N>::passes(); }
+  static constexpr int radix(int q) { return StaticPlan<N>::radix(REV ? passes() - 1 - q : q); }
+  static constexpr int span(int q) {
+    int s = 1;
+    for (int i = 0; i < q; ++i) s *= radix(i);
+    return s;
+  }
+};
+
+// Passes [Q, QE) of the compiled transform of length N in the given order.
+template <int N, int NL, bool LF, int EM, bool PD, bool REV, int Q, int QE>
+__device__ __forceinline__ void static_passes(float2* lds, int nl_rt, int es, int ls, int shift,
+                                              const float2* tw, float s, int tid, int nthr) {
+  if constexpr (Q < QE) {
+    using PL = OrderedPlan<N, REV>;
+    static_pass<N, PL::radix(Q), PL::span(Q), NL, LF, EM, PD>(lds, nl_rt, es, ls, shift, tw, s, tid,
+                                                             nthr);
+    static_passes<N, NL, LF, EM, PD, REV, Q + 1, QE>(lds, nl_rt, es, ls, shift, tw, s, tid, nthr);
+  }
+}
+
+// Transform of the lines of length N (compiled stages, forward radix order)
+// whose first pass takes its inputs from load(l, i) and whose last pass hands
+// its outputs to store(l, i, v) (line l, element i): LDS (layout as in
+// LdsLines: line base l * ls, element i at i * es, or the padded row slot)
+// holds the data only between passes, which halves its traffic for a
+// three-pass length.  load() is called for every input of the thread before
+// any butterfly (keep it free of data-dependent branches so the loads are in
+// flight together); mid() runs after the loads are issued (the twiddle table
+// the later passes read must be filled there or before).  Every thread calls
+// it; it synchronises internally and leaves LDS free on return.
+template <int N, int NL, bool LF, int EM, bool PD, typename LD, typename MID, typename ST>
+__device__ __forceinline__ void fft_direct(float2* lds, int nl_rt, int es, int ls, int shift,
+                                           const float2* tw, float s, int tid, int nthr, LD load,
+                                           MID mid, ST store) {
+  constexpr int NP = StaticPlan<N>::passes();
+  static_assert(NP >= 2, "fft_direct needs at least two passes");
+  constexpr int R0 = StaticPlan<N>::radix(0), NB0 = N / R0;
+  constexpr int RL = StaticPlan<N>::radix(NP - 1), NSL = N / RL;
+  constexpr int B0 = (EM + R0 - 1) / R0, BL = (EM + RL - 1) / RL;
+  const int nl = NL > 0 ? NL : nl_rt;
+  auto line_of = [&](int j, int nb, int& l, int& k) {
+    if (LF) {
+      if (NL == 0 && shift >= 0) { l = j & (nl - 1); k = j >> shift; }
+      else { l = j % nl; k = j / nl; }
+    } else {
+      k = j % nb;
+      l = j / nb;
+    }
+  };
+  auto at = [&](int l, int i) { return l * ls + (PD ? row_slot(i, pad_shift(N)) : i * es); };
+  float2 v[B0][R0];
+#pragma unroll
+  for (int b = 0; b < B0; ++b) {
+    const int j = tid + b * nthr;
+    if (j < nl * NB0) {
+      int l, k;
+      line_of(j, NB0, l, k);
+#pragma unroll
+      for (int r = 0; r < R0; ++r) v[b][r] = load(l, k + r * NB0);
+    }
+  }
+  mid();
+#pragma unroll
+  for (int b = 0; b < B0; ++b) {
+    const int j = tid + b * nthr;
+    if (j < nl * NB0) {
+      int l, k;
+      line_of(j, NB0, l, k);
+      dft_small<R0>(v[b], s);   // span 1: no twiddles
+#pragma unroll
+      for (int r = 0; r < R0; ++r) lds[at(l, k * R0 + r)] = v[b][r];
+    }
+  }
+  __syncthreads();
+  static_passes<N, NL, LF, EM, PD, false, 1, NP - 1>(lds, nl_rt, es, ls, shift, tw, s, tid, nthr);
+#pragma unroll
+  for (int b = 0; b < BL; ++b) {
+    const int j = tid + b * nthr;
+    if (j < nl * NSL) {
+      int l, k;
+      line_of(j, NSL, l, k);
+      float2 w[RL];
+      float2 w1 = tw[k];   // span NSL: twiddle stride 1
+      if (s > 0.f) w1.y = -w1.y;
+      twiddle_powers<RL>(w, w1);
+      float2 x[RL];
+#pragma unroll
+      for (int r = 0; r < RL; ++r) {
+        x[r] = lds[at(l, k + r * NSL)];
+        if (r > 0) x[r] = cmul(x[r], w[r]);
+      }
+      dft_small<RL>(x, s);
+#pragma unroll
+      for (int r = 0; r < RL; ++r) store(l, k + r * NSL, x[r]);
+    }
+  }
+  __syncthreads();
+}
+
 // FFT of the lines described by L: static length NSTAT (> 0) or the runtime plan
 // (NSTAT == 0).  NL > 0 fixes the number of lines; LF must equal L.linefast.
 // EM bounds the elements a thread owns (lines * n <= threads * EM) for the

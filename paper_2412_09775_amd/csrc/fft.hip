@@ -243,16 +243,28 @@ __global__ __launch_bounds__(1024) void k_cols(float2* __restrict__ data, int N,
   const long m0 = tile * W;
   const int weff = (int)min((long)W, M - m0);
   const int Nc = NS > 0 ? NS : N;
-  gather_to_lds(buf, Nc * W, tid, nthr, [&](int e) {
-    const int n = e >> wsh, w = e & (W - 1);
-    return w < weff ? base[(long)n * M + m0 + w] : make_float2(0.f, 0.f);
-  }, [&] { fill_twiddles(tw, Nc, tid, nthr); });
-  __syncthreads();
-  fft_lines<NS, WS, true>(buf, LdsLines{W, W, 1, true, wsh}, plan, tw, sign, tid, nthr);
-  scatter_from_lds(buf, Nc * W, tid, nthr, [&](int e, float2 v) {
-    const int n = e >> wsh, w = e & (W - 1);
-    if (w < weff) base[(long)n * M + m0 + w] = v;
-  });
+  if constexpr (NS > 0) {
+    // line l = column m0 + l; first pass straight from memory, last pass
+    // straight to memory
+    fft_direct<NS, WS, true, kEmax, false>(
+        buf, W, W, 1, wsh, tw, sign, tid, nthr,
+        [&](int l, int n) { return l < weff ? base[(long)n * M + m0 + l] : make_float2(0.f, 0.f); },
+        [&] { fill_twiddles(tw, Nc, tid, nthr); },
+        [&](int l, int n, float2 v) {
+          if (l < weff) base[(long)n * M + m0 + l] = v;
+        });
+  } else {
+    gather_to_lds(buf, Nc * W, tid, nthr, [&](int e) {
+      const int n = e >> wsh, w = e & (W - 1);
+      return w < weff ? base[(long)n * M + m0 + w] : make_float2(0.f, 0.f);
+    }, [&] { fill_twiddles(tw, Nc, tid, nthr); });
+    __syncthreads();
+    fft_lines<NS, WS, true>(buf, LdsLines{W, W, 1, true, wsh}, plan, tw, sign, tid, nthr);
+    scatter_from_lds(buf, Nc * W, tid, nthr, [&](int e, float2 v) {
+      const int n = e >> wsh, w = e & (W - 1);
+      if (w < weff) base[(long)n * M + m0 + w] = v;
+    });
+  }
 }
 
 // Column tile width: W contiguous complex values per row (W = 16 is one

@@ -110,84 +110,203 @@ __global__ __launch_bounds__(1024) void k_tf_fields_y(const DevOptics* __restric
   constexpr int EPT = kEmax / NF;   // elements of a thread: Y * W * NF <= threads * kEmax
   const int x0 = (int)(tile * W);
   const int wsh = pow2_shift(W);     // W is a power of two
-  // z-independent factors of this thread's elements e = tid + i * nthr
-  double tkz[EPT], sp[EPT], gg[fluor ? 1 : EPT];
-  {
-    const double hw = soft_halfwidth(o, sm);
-    const double km = o.n_medium / o.wavelength;
-    const double rd = o.na_det / o.wavelength, ri = o.na_ill / o.wavelength;
-    double cy, cx;
-    source_centre(o, &cy, &cx);
-    double psum = 0.0;
+  const int nl = nf * W;              // lines of the tile: field f, column w (l = f W + w)
+  const int lsh = pow2_shift(nl);
+  if constexpr (NS > 0) {
+    // The first pass of the inverse Y transform takes its inputs from registers
+    // (the fields are computed where the butterfly needs them) and the last
+    // pass writes to memory from registers: LDS carries only the passes
+    // between.  Butterfly j of the first pass: line l = j mod nl, elements
+    // ky = k + r NB0 (k = j / nl); of the last pass: outputs ky = k + r NSL.
+    constexpr int NP = StaticPlan<NS>::passes();
+    constexpr int R0 = StaticPlan<NS>::radix(0), NB0 = NS / R0;
+    constexpr int RL = StaticPlan<NS>::radix(NP - 1), NSL = NS / RL;
+    constexpr int B0 = (kEmax + R0 - 1) / R0, BL = (kEmax + RL - 1) / RL;
+    static_assert(NP >= 2, "compiled lateral lengths have at least two passes");
+    double tkz[B0][R0];
+    float fac[B0][R0];
+    {
+      const double hw = soft_halfwidth(o, sm);
+      const double km = o.n_medium / o.wavelength;
+      const double rd = o.na_det / o.wavelength, ri = o.na_ill / o.wavelength;
+      double cy, cx;
+      source_centre(o, &cy, &cx);
+      double psum = 0.0;
 #pragma unroll
-    for (int i = 0; i < EPT; ++i) {
-      tkz[i] = 0.0;
-      sp[i] = 0.0;
-      if (!fluor) gg[i] = 0.0;
-      const int e = tid + i * nthr;
-      if (e < Y * W) {
-        const int ky = e >> wsh, w = e & (W - 1);
-        const int kx = x0 + w;
-        if (kx < X) {
-          const double fy = fftfreq(ky, Y, sm.dy), fx = fftfreq(kx, X, sm.dx);
-          const double P = disc(fy, fx, rd, hw);
-          if (P != 0.0) {
-            const double kz = sqrt(fmax(km * km - (fy * fy + fx * fx), 0.0));
-            tkz[i] = 2.0 * kz;
-            if (fluor) {
-              sp[i] = P;
-              psum += P * P;
-            } else {
-              double S = disc(fy - cy, fx - cx, ri, hw);
-              if (o.sector >= 0 && octant(fy - cy, fx - cx) != o.sector) S = 0.0;
-              psum += S * P * P;
-              sp[i] = S * P;
-              if (kz > 0.0) gg[i] = P * km / kz;   // P * (i k_m / kz)
+      for (int b = 0; b < B0; ++b) {
+        const int j = tid + b * nthr;
+        const int l = j & (nl - 1), k = j >> lsh;
+        const int f = l >> wsh, kx = x0 + (l & (W - 1));
+#pragma unroll
+        for (int r = 0; r < R0; ++r) {
+          tkz[b][r] = 0.0;
+          fac[b][r] = 0.f;
+          if (j < nl * NB0 && kx < X) {
+            const int ky = k + r * NB0;
+            const double fy = fftfreq(ky, Y, sm.dy), fx = fftfreq(kx, X, sm.dx);
+            const double P = disc(fy, fx, rd, hw);
+            if (P != 0.0) {
+              const double kz = sqrt(fmax(km * km - (fy * fy + fx * fx), 0.0));
+              tkz[b][r] = 2.0 * kz;
+              if (fluor) {
+                fac[b][r] = (float)P;
+                psum += P * P;
+              } else {
+                double S = disc(fy - cy, fx - cx, ri, hw);
+                if (o.sector >= 0 && octant(fy - cy, fx - cx) != o.sector) S = 0.0;
+                if (f == 0) {
+                  fac[b][r] = (float)(S * P);
+                  psum += S * P * P;
+                } else if (kz > 0.0) {
+                  fac[b][r] = (float)(P * km / kz);   // P * (i k_m / kz)
+                }
+              }
             }
           }
         }
       }
-    }
-    if (zc == 0) {
-      const double tot = block_sum(psum, red);
-      if (tid == 0) partials[patch * tiles_x + tile] = tot;
-    }
-  }
-  const int zend = min(Z, (zc + 1) * ZC);
-  for (int z = zc * ZC; z < zend; ++z) {
-    const double dzr = plane_z(z, sm) - o.defocus;
-#pragma unroll
-    for (int i = 0; i < EPT; ++i) {
-      const int e = tid + i * nthr;
-      if (e < Y * W) {
-        const int ky = e >> wsh, w = e & (W - 1);
-        float2 A = make_float2(0.f, 0.f), B = make_float2(0.f, 0.f);
-        if (sp[i] != 0.0 || (!fluor && gg[i] != 0.0)) {
-          // phase 2 pi kz (z - dz0): reduce the argument (in units of pi) in FP64
-          // to [-1, 1], then evaluate sin/cos in FP32
-          const double arg = tkz[i] * dzr;
-          const float rr = (float)(arg - 2.0 * rint(0.5 * arg));
-          float snf, csf;
-          sincospif(rr, &snf, &csf);
-          const double sn = snf, cs = csf;
-          A = make_float2((float)(sp[i] * cs), (float)(sp[i] * sn));
-          if (!fluor) B = make_float2((float)(-gg[i] * sn), (float)(gg[i] * cs));   // e^{i phi} (i g)
-        }
-        buf[ky * nf * W + w] = A;
-        if (!fluor) buf[ky * nf * W + W + w] = B;
+      if (zc == 0) {
+        const double tot = block_sum(psum, red);
+        if (tid == 0) partials[patch * tiles_x + tile] = tot;
       }
     }
-    __syncthreads();
-    fft_lines<NS, 0, true>(buf, LdsLines{nf * W, nf * W, 1, true, pow2_shift(nf * W)}, plan, tw, 1.f,
-                           tid, nthr);
-    scatter_from_lds(buf, Y * nf * W, tid, nthr, [&](int e, float2 v) {
-      const int ky = e >> (wsh + nf - 1);
-      const int r = e & (nf * W - 1);
-      const int f = r >> wsh, w = r & (W - 1);
-      const int kx = x0 + w;
-      if (kx < X) ab[(((patch * nf + f) * Z + z) * (long)Y + ky) * X + kx] = v;
-    });
-    __syncthreads();
+    const int zend = min(Z, (zc + 1) * ZC);
+    for (int z = zc * ZC; z < zend; ++z) {
+      const double dzr = plane_z(z, sm) - o.defocus;
+#pragma unroll
+      for (int b = 0; b < B0; ++b) {
+        const int j = tid + b * nthr;
+        if (j < nl * NB0) {
+          const int l = j & (nl - 1), k = j >> lsh;
+          const bool fa = (l >> wsh) == 0;   // A (or the fluorescence field), else B
+          float2 v[R0];
+#pragma unroll
+          for (int r = 0; r < R0; ++r) {
+            v[r] = make_float2(0.f, 0.f);
+            if (fac[b][r] != 0.f) {
+              // phase 2 pi kz (z - dz0): reduce the argument (in units of pi) in
+              // FP64 to [-1, 1], then evaluate sin/cos in FP32
+              const double arg = tkz[b][r] * dzr;
+              const float rr = (float)(arg - 2.0 * rint(0.5 * arg));
+              float sn, cs;
+              sincospif(rr, &sn, &cs);
+              v[r] = fa ? make_float2(fac[b][r] * cs, fac[b][r] * sn)
+                        : make_float2(-fac[b][r] * sn, fac[b][r] * cs);   // e^{i phi} (i g)
+            }
+          }
+          dft_small<R0>(v, 1.f);   // span 1: no twiddles
+#pragma unroll
+          for (int r = 0; r < R0; ++r) buf[l + (k * R0 + r) * nl] = v[r];
+        }
+      }
+      __syncthreads();
+      static_passes<NS, 0, true, kEmax, false, false, 1, NP - 1>(buf, nl, nl, 1, lsh, tw, 1.f, tid, nthr);
+#pragma unroll
+      for (int b = 0; b < BL; ++b) {
+        const int j = tid + b * nthr;
+        if (j < nl * NSL) {
+          const int l = j & (nl - 1), k = j >> lsh;
+          float2 w[RL];
+          float2 w1 = tw[k];   // span NSL = NS / RL: twiddle stride 1; conjugate for the inverse
+          w1.y = -w1.y;
+          twiddle_powers<RL>(w, w1);
+          float2 v[RL];
+#pragma unroll
+          for (int r = 0; r < RL; ++r) {
+            v[r] = buf[l + (k + r * NSL) * nl];
+            if (r > 0) v[r] = cmul(v[r], w[r]);
+          }
+          dft_small<RL>(v, 1.f);
+          const int f = l >> wsh, kx = x0 + (l & (W - 1));
+          if (kx < X) {
+            float2* dst = ab + ((patch * nf + f) * Z + z) * (long)Y * X + kx;
+#pragma unroll
+            for (int r = 0; r < RL; ++r) dst[(long)(k + r * NSL) * X] = v[r];
+          }
+        }
+      }
+      __syncthreads();   // the next plane's first pass writes the same LDS
+    }
+  } else {
+    // z-independent factors of this thread's elements e = tid + i * nthr
+    double tkz[EPT], sp[EPT], gg[fluor ? 1 : EPT];
+    {
+      const double hw = soft_halfwidth(o, sm);
+      const double km = o.n_medium / o.wavelength;
+      const double rd = o.na_det / o.wavelength, ri = o.na_ill / o.wavelength;
+      double cy, cx;
+      source_centre(o, &cy, &cx);
+      double psum = 0.0;
+#pragma unroll
+      for (int i = 0; i < EPT; ++i) {
+        tkz[i] = 0.0;
+        sp[i] = 0.0;
+        if (!fluor) gg[i] = 0.0;
+        const int e = tid + i * nthr;
+        if (e < Y * W) {
+          const int ky = e >> wsh, w = e & (W - 1);
+          const int kx = x0 + w;
+          if (kx < X) {
+            const double fy = fftfreq(ky, Y, sm.dy), fx = fftfreq(kx, X, sm.dx);
+            const double P = disc(fy, fx, rd, hw);
+            if (P != 0.0) {
+              const double kz = sqrt(fmax(km * km - (fy * fy + fx * fx), 0.0));
+              tkz[i] = 2.0 * kz;
+              if (fluor) {
+                sp[i] = P;
+                psum += P * P;
+              } else {
+                double S = disc(fy - cy, fx - cx, ri, hw);
+                if (o.sector >= 0 && octant(fy - cy, fx - cx) != o.sector) S = 0.0;
+                psum += S * P * P;
+                sp[i] = S * P;
+                if (kz > 0.0) gg[i] = P * km / kz;   // P * (i k_m / kz)
+              }
+            }
+          }
+        }
+      }
+      if (zc == 0) {
+        const double tot = block_sum(psum, red);
+        if (tid == 0) partials[patch * tiles_x + tile] = tot;
+      }
+    }
+    const int zend = min(Z, (zc + 1) * ZC);
+    for (int z = zc * ZC; z < zend; ++z) {
+      const double dzr = plane_z(z, sm) - o.defocus;
+#pragma unroll
+      for (int i = 0; i < EPT; ++i) {
+        const int e = tid + i * nthr;
+        if (e < Y * W) {
+          const int ky = e >> wsh, w = e & (W - 1);
+          float2 A = make_float2(0.f, 0.f), B = make_float2(0.f, 0.f);
+          if (sp[i] != 0.0 || (!fluor && gg[i] != 0.0)) {
+            // phase 2 pi kz (z - dz0): reduce the argument (in units of pi) in FP64
+            // to [-1, 1], then evaluate sin/cos in FP32
+            const double arg = tkz[i] * dzr;
+            const float rr = (float)(arg - 2.0 * rint(0.5 * arg));
+            float snf, csf;
+            sincospif(rr, &snf, &csf);
+            const double sn = snf, cs = csf;
+            A = make_float2((float)(sp[i] * cs), (float)(sp[i] * sn));
+            if (!fluor) B = make_float2((float)(-gg[i] * sn), (float)(gg[i] * cs));   // e^{i phi} (i g)
+          }
+          buf[ky * nf * W + w] = A;
+          if (!fluor) buf[ky * nf * W + W + w] = B;
+        }
+      }
+      __syncthreads();
+      fft_lines<NS, 0, true>(buf, LdsLines{nf * W, nf * W, 1, true, pow2_shift(nf * W)}, plan, tw, 1.f,
+                             tid, nthr);
+      scatter_from_lds(buf, Y * nf * W, tid, nthr, [&](int e, float2 v) {
+        const int ky = e >> (wsh + nf - 1);
+        const int r = e & (nf * W - 1);
+        const int f = r >> wsh, w = r & (W - 1);
+        const int kx = x0 + w;
+        if (kx < X) ab[(((patch * nf + f) * Z + z) * (long)Y + ky) * X + kx] = v;
+      });
+      __syncthreads();
+    }
   }
 }
 
@@ -293,17 +412,76 @@ __global__ __launch_bounds__(1024) void k_tf_rows_lf(const double* __restrict__ 
     return t * LS + row_slot(e - t * X, PS);
   }, [&] { wave0_sum(partials + patch * tiles_x, tiles_x, &ibg_s); });   // sum S P^2
   __syncthreads();
-  fft_lines<NS, 0, false, kEmax, true>(buf, LdsLines{2 * nr, 1, LS, false, -1, true}, plan, tw, 1.f,
-                                       tid, nthr);
   const float cs = (float)(1.0 / ((double)X * (double)Y * ibg_s));
-  for (int e = tid; e < nr * X; e += nthr) {
-    const int r = e / X, i = row_slot(e - r * X, PS);
-    const float2 a = buf[2 * r * LS + i], b = buf[(2 * r + 1) * LS + i];
-    buf[2 * r * LS + i] = cscale(cmulconj(b, a), cs);
+  if constexpr (NS > 0) {
+    // Inverse transforms of a and b in reversed radix order up to their last
+    // pass; that pass, the product c = b conj(a) / (X Y I_bg) and the first
+    // pass of the forward transform of c run in registers (the outputs of the
+    // one are the inputs of the other, k + i NB); c goes to line 2r.
+    constexpr int NP = StaticPlan<NS>::passes();
+    constexpr int R0 = StaticPlan<NS>::radix(0);
+    constexpr int NB = NS / R0;
+    constexpr int BPF = (kEmax + 2 * R0 - 1) / (2 * R0);   // butterflies of a thread
+    static_passes<NS, 0, false, kEmax, true, true, 0, NP - 1>(buf, 2 * nr, 1, LS, -1, tw, 1.f, tid,
+                                                              nthr);
+    float2 cv[BPF][R0];
+    int cr[BPF], ck[BPF];
+#pragma unroll
+    for (int b = 0; b < BPF; ++b) {
+      const int j = tid + b * nthr;
+      cr[b] = -1;
+      if (j < nr * NB) {
+        const int r = j / NB, k = j - r * NB;
+        float2 w[R0];
+        if constexpr (NP > 1) {
+          float2 w1 = tw[k];   // span NB, twiddle stride 1; conjugate for the inverse
+          w1.y = -w1.y;
+          twiddle_powers<R0>(w, w1);
+        }
+        float2 va[R0], vb[R0];
+#pragma unroll
+        for (int i = 0; i < R0; ++i) {
+          const int sl = row_slot(k + i * NB, PS);
+          va[i] = buf[2 * r * LS + sl];
+          vb[i] = buf[(2 * r + 1) * LS + sl];
+          if constexpr (NP > 1) {
+            if (i > 0) {
+              va[i] = cmul(va[i], w[i]);
+              vb[i] = cmul(vb[i], w[i]);
+            }
+          }
+        }
+        dft_small<R0>(va, 1.f);
+        dft_small<R0>(vb, 1.f);
+#pragma unroll
+        for (int i = 0; i < R0; ++i) cv[b][i] = cscale(cmulconj(vb[i], va[i]), cs);
+        dft_small<R0>(cv[b], -1.f);
+        cr[b] = r;
+        ck[b] = k;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int b = 0; b < BPF; ++b) {
+      if (cr[b] >= 0) {
+#pragma unroll
+        for (int i = 0; i < R0; ++i) buf[2 * cr[b] * LS + row_slot(ck[b] * R0 + i, PS)] = cv[b][i];
+      }
+    }
+    __syncthreads();
+    static_passes<NS, 0, false, kEmax, true, false, 1, NP>(buf, nr, 1, 2 * LS, -1, tw, -1.f, tid, nthr);
+  } else {
+    fft_lines<NS, 0, false, kEmax, true>(buf, LdsLines{2 * nr, 1, LS, false, -1, true}, plan, tw, 1.f,
+                                         tid, nthr);
+    for (int e = tid; e < nr * X; e += nthr) {
+      const int r = e / X, i = row_slot(e - r * X, PS);
+      const float2 a = buf[2 * r * LS + i], b = buf[(2 * r + 1) * LS + i];
+      buf[2 * r * LS + i] = cscale(cmulconj(b, a), cs);
+    }
+    __syncthreads();
+    fft_lines<NS, 0, false, kEmax, true>(buf, LdsLines{nr, 1, 2 * LS, false, -1, true}, plan, tw, -1.f,
+                                         tid, nthr);
   }
-  __syncthreads();
-  fft_lines<NS, 0, false, kEmax, true>(buf, LdsLines{nr, 1, 2 * LS, false, -1, true}, plan, tw, -1.f,
-                                       tid, nthr);
   float2* op = out + patch * patch_stride;
   for (int e = tid; e < nr * Xh; e += nthr) {
     const int r = e / Xh, k = e - r * Xh;
