@@ -201,15 +201,22 @@ __global__ __launch_bounds__(1024) void k_tf_rows_bwd(const double* __restrict__
   const double tot = block_sum_d(dsum, red);
   if (tid == 0) dpart[v * wg_per_patch + wg] = tot;
   __syncthreads();
-  fft_lines<NS, 0, false, kEmax, true>(buf, LdsLines{2 * nr, 1, LS, false, -1, true}, plan, tw, 1.f,
-                                       tid, nthr);
-  scatter_from_lds_map(buf, nr * 2 * X, tid, nthr, slot, [&](int e, float2 val) {
-    const int i = e % X;
-    const int t = e / X;
-    const int f = t & 1, r = t >> 1;
-    float2* dst = f ? b_src : a_src;
-    dst[(row0 + r) * X + i] = val;
-  });
+  auto store = [&](int t, int i, float2 val) {
+    ((t & 1) ? b_src : a_src)[(row0 + (t >> 1)) * X + i] = val;
+  };
+  if constexpr (NS > 0) {
+    // last pass straight to memory
+    static_passes<NS, 0, false, kEmax, true, false, 0, StaticPlan<NS>::passes() - 1>(
+        buf, 2 * nr, 1, LS, -1, tw, 1.f, tid, nthr);
+    last_pass_out<NS, 0, false, kEmax, true, false>(buf, 2 * nr, 1, LS, -1, tw, 1.f, tid, nthr, store);
+  } else {
+    fft_lines<NS, 0, false, kEmax, true>(buf, LdsLines{2 * nr, 1, LS, false, -1, true}, plan, tw, 1.f,
+                                         tid, nthr);
+    scatter_from_lds_map(buf, nr * 2 * X, tid, nthr, slot, [&](int e, float2 val) {
+      const int t = e / X;
+      store(t, e - t * X, val);
+    });
+  }
 }
 
 // Rows per workgroup of the backward row kernel (three LDS lines per row):

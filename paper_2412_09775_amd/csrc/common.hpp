@@ -643,45 +643,53 @@ __device__ __forceinline__ void static_passes(float2* lds, int nl_rt, int es, in
   }
 }
 
-// Transform of the lines of length N (compiled stages, forward radix order)
-// whose first pass takes its inputs from load(l, i) and whose last pass hands
-// its outputs to store(l, i, v) (line l, element i): LDS (layout as in
-// LdsLines: line base l * ls, element i at i * es, or the padded row slot)
-// holds the data only between passes, which halves its traffic for a
-// three-pass length.  load() is called for every input of the thread before
-// any butterfly (keep it free of data-dependent branches so the loads are in
-// flight together); mid() runs after the loads are issued (the twiddle table
-// the later passes read must be filled there or before).  Every thread calls
-// it; it synchronises internally and leaves LDS free on return.
-template <int N, int NL, bool LF, int EM, bool PD, typename LD, typename MID, typename ST>
-__device__ __forceinline__ void fft_direct(float2* lds, int nl_rt, int es, int ls, int shift,
-                                           const float2* tw, float s, int tid, int nthr, LD load,
-                                           MID mid, ST store) {
-  constexpr int NP = StaticPlan<N>::passes();
-  static_assert(NP >= 2, "fft_direct needs at least two passes");
-  constexpr int R0 = StaticPlan<N>::radix(0), NB0 = N / R0;
-  constexpr int RL = StaticPlan<N>::radix(NP - 1), NSL = N / RL;
-  constexpr int B0 = (EM + R0 - 1) / R0, BL = (EM + RL - 1) / RL;
+// First and last pass of a compiled transform through registers.
+//
+// first_pass_in: the first pass (span 1, no twiddles) of the lines of length N
+// in the given radix order takes its inputs from load(l, i) (line l, element
+// i; first_pass_in2: finish(l, i, load(l, i)), finish applied after every load
+// of the thread is issued) and writes its outputs to LDS (layout as in LdsLines: line base l * ls,
+// element i at i * es, or the padded row slot); load() is called for every
+// input of the thread before any butterfly (keep it free of data-dependent
+// branches so the loads are in flight together) and mid() runs after the
+// loads are issued (fill the twiddle table there or before).  Ends with a
+// barrier.
+//
+// last_pass_out: the last pass reads LDS and hands its outputs to
+// store(l, i, v) (memory or registers, not the same LDS: other threads may
+// still read it).  Ends with a barrier.
+//
+// Between them static_passes runs the passes in LDS; fft_direct is the three
+// together, which halves the LDS traffic of a three-pass length.
+template <int N, int NL, bool LF, bool PD>
+__device__ __forceinline__ void line_of(int j, int nl, int nb, int shift, int& l, int& k) {
+  if (LF) {
+    if (NL == 0 && shift >= 0) { l = j & (nl - 1); k = j >> shift; }
+    else { l = j % nl; k = j / nl; }
+  } else {
+    k = j % nb;
+    l = j / nb;
+  }
+}
+
+template <int N, int NL, bool LF, int EM, bool PD, bool REV, typename LD, typename FIN, typename MID>
+__device__ __forceinline__ void first_pass_in2(float2* lds, int nl_rt, int es, int ls, int shift,
+                                               float s, int tid, int nthr, LD load, FIN finish,
+                                               MID mid) {
+  using PL = OrderedPlan<N, REV>;
+  constexpr int R0 = PL::radix(0), NB0 = N / R0;
+  constexpr int B0 = (EM + R0 - 1) / R0;
+  using T = decltype(load(0, 0));
   const int nl = NL > 0 ? NL : nl_rt;
-  auto line_of = [&](int j, int nb, int& l, int& k) {
-    if (LF) {
-      if (NL == 0 && shift >= 0) { l = j & (nl - 1); k = j >> shift; }
-      else { l = j % nl; k = j / nl; }
-    } else {
-      k = j % nb;
-      l = j / nb;
-    }
-  };
-  auto at = [&](int l, int i) { return l * ls + (PD ? row_slot(i, pad_shift(N)) : i * es); };
-  float2 v[B0][R0];
+  T raw[B0][R0];
 #pragma unroll
   for (int b = 0; b < B0; ++b) {
     const int j = tid + b * nthr;
     if (j < nl * NB0) {
       int l, k;
-      line_of(j, NB0, l, k);
+      line_of<N, NL, LF, PD>(j, nl, NB0, shift, l, k);
 #pragma unroll
-      for (int r = 0; r < R0; ++r) v[b][r] = load(l, k + r * NB0);
+      for (int r = 0; r < R0; ++r) raw[b][r] = load(l, k + r * NB0);
     }
   }
   mid();
@@ -690,28 +698,50 @@ __device__ __forceinline__ void fft_direct(float2* lds, int nl_rt, int es, int l
     const int j = tid + b * nthr;
     if (j < nl * NB0) {
       int l, k;
-      line_of(j, NB0, l, k);
-      dft_small<R0>(v[b], s);   // span 1: no twiddles
+      line_of<N, NL, LF, PD>(j, nl, NB0, shift, l, k);
+      float2 v[R0];
 #pragma unroll
-      for (int r = 0; r < R0; ++r) lds[at(l, k * R0 + r)] = v[b][r];
+      for (int r = 0; r < R0; ++r) v[r] = finish(l, k + r * NB0, raw[b][r]);
+      dft_small<R0>(v, s);
+#pragma unroll
+      for (int r = 0; r < R0; ++r)
+        lds[l * ls + (PD ? row_slot(k * R0 + r, pad_shift(N)) : (k * R0 + r) * es)] = v[r];
     }
   }
   __syncthreads();
-  static_passes<N, NL, LF, EM, PD, false, 1, NP - 1>(lds, nl_rt, es, ls, shift, tw, s, tid, nthr);
+}
+
+// As first_pass_in2 with the loaded values used as they are.
+template <int N, int NL, bool LF, int EM, bool PD, bool REV, typename LD, typename MID>
+__device__ __forceinline__ void first_pass_in(float2* lds, int nl_rt, int es, int ls, int shift,
+                                              float s, int tid, int nthr, LD load, MID mid) {
+  first_pass_in2<N, NL, LF, EM, PD, REV>(lds, nl_rt, es, ls, shift, s, tid, nthr, load,
+                                         [](int, int, float2 v) { return v; }, mid);
+}
+
+template <int N, int NL, bool LF, int EM, bool PD, bool REV, typename ST>
+__device__ __forceinline__ void last_pass_out(const float2* lds, int nl_rt, int es, int ls, int shift,
+                                              const float2* tw, float s, int tid, int nthr, ST store) {
+  using PL = OrderedPlan<N, REV>;
+  constexpr int NP = PL::passes();
+  constexpr int RL = PL::radix(NP - 1), NSL = N / RL;
+  constexpr int BL = (EM + RL - 1) / RL;
+  const int nl = NL > 0 ? NL : nl_rt;
 #pragma unroll
   for (int b = 0; b < BL; ++b) {
     const int j = tid + b * nthr;
     if (j < nl * NSL) {
       int l, k;
-      line_of(j, NSL, l, k);
+      line_of<N, NL, LF, PD>(j, nl, NSL, shift, l, k);
       float2 w[RL];
-      float2 w1 = tw[k];   // span NSL: twiddle stride 1
+      float2 w1 = tw[k];   // span NSL = N / RL: twiddle stride 1
       if (s > 0.f) w1.y = -w1.y;
       twiddle_powers<RL>(w, w1);
       float2 x[RL];
 #pragma unroll
       for (int r = 0; r < RL; ++r) {
-        x[r] = lds[at(l, k + r * NSL)];
+        const int i = k + r * NSL;
+        x[r] = lds[l * ls + (PD ? row_slot(i, pad_shift(N)) : i * es)];
         if (r > 0) x[r] = cmul(x[r], w[r]);
       }
       dft_small<RL>(x, s);
@@ -720,6 +750,17 @@ __device__ __forceinline__ void fft_direct(float2* lds, int nl_rt, int es, int l
     }
   }
   __syncthreads();
+}
+
+template <int N, int NL, bool LF, int EM, bool PD, typename LD, typename MID, typename ST>
+__device__ __forceinline__ void fft_direct(float2* lds, int nl_rt, int es, int ls, int shift,
+                                           const float2* tw, float s, int tid, int nthr, LD load,
+                                           MID mid, ST store) {
+  constexpr int NP = StaticPlan<N>::passes();
+  static_assert(NP >= 2, "fft_direct needs at least two passes");
+  first_pass_in<N, NL, LF, EM, PD, false>(lds, nl_rt, es, ls, shift, s, tid, nthr, load, mid);
+  static_passes<N, NL, LF, EM, PD, false, 1, NP - 1>(lds, nl_rt, es, ls, shift, tw, s, tid, nthr);
+  last_pass_out<N, NL, LF, EM, PD, false>(lds, nl_rt, es, ls, shift, tw, s, tid, nthr, store);
 }
 
 // FFT of the lines described by L: static length NSTAT (> 0) or the runtime plan

@@ -40,20 +40,29 @@ __global__ __launch_bounds__(1024) void k_rows_r2c(const float* __restrict__ in,
   const int LS = row_stride(Xc);    // padded line pitch in LDS
   // a missing second row (odd row count) loads the first row again and is
   // zeroed after the loads
-  gather2_to_lds(buf, nl * Xc, tid, nthr, [&](int e) {
-    const int l = e / Xc, i = e - l * Xc;
+  auto load = [&](int l, int i) {
     const long ra = rin[2 * l], rb = rin[2 * l + 1];
     return make_float2(in[ra * X + i], in[(rb >= 0 ? rb : ra) * X + i]);
-  }, [&](int e, float2 v) {
-    const int l = e / Xc;
-    return make_float2(v.x, rin[2 * l + 1] >= 0 ? v.y : 0.f);
-  }, [&](int e) {
-    const int l = e / Xc;
-    return l * LS + row_slot(e - l * Xc, PS);
-  }, [&] { fill_twiddles(tw, X, tid, nthr); });
-  __syncthreads();
-  fft_lines<NS, 0, false, kEmax, true>(buf, LdsLines{nl, 1, LS, false, -1, true}, plan, tw, -1.f, tid,
-                                       nthr);
+  };
+  auto finish = [&](int l, int, float2 v) { return make_float2(v.x, rin[2 * l + 1] >= 0 ? v.y : 0.f); };
+  if constexpr (NS > 0) {
+    // first pass straight from memory
+    first_pass_in2<NS, 0, false, kEmax, true, false>(buf, nl, 1, LS, -1, -1.f, tid, nthr, load, finish,
+                                                     [&] { fill_twiddles(tw, X, tid, nthr); });
+    static_passes<NS, 0, false, kEmax, true, false, 1, StaticPlan<NS>::passes()>(buf, nl, 1, LS, -1, tw,
+                                                                                -1.f, tid, nthr);
+  } else {
+    gather2_to_lds(buf, nl * Xc, tid, nthr, [&](int e) {
+      const int l = e / Xc;
+      return load(l, e - l * Xc);
+    }, [&](int e, float2 v) { return finish(e / Xc, 0, v); }, [&](int e) {
+      const int l = e / Xc;
+      return l * LS + row_slot(e - l * Xc, PS);
+    }, [&] { fill_twiddles(tw, X, tid, nthr); });
+    __syncthreads();
+    fft_lines<NS, 0, false, kEmax, true>(buf, LdsLines{nl, 1, LS, false, -1, true}, plan, tw, -1.f, tid,
+                                         nthr);
+  }
   const int Xh = Xc / 2 + 1;
 #pragma unroll
   for (int i = 0; i < kEmax; ++i) {
@@ -97,15 +106,14 @@ __global__ __launch_bounds__(1024) void k_rows_c2r(const float2* __restrict__ in
     const int l = e / Xc;
     return l * LS + row_slot(e - l * Xc, PS);
   };
-  gather2_to_lds(buf, nl * Xc, tid, nthr, [&](int e) {
-    const int l = e / Xc, k = e - l * Xc;
+  auto load = [&](int l, int k) {
     const int kk = 2 * k > Xc ? Xc - k : k;
     const long ra = rin[2 * l], rb = rin[2 * l + 1];
     const float2 A = in[ra * Xh + kk];
     const float2 B = in[(rb >= 0 ? rb : ra) * Xh + kk];
     return make_float4(A.x, A.y, B.x, B.y);
-  }, [&](int e, float4 v) {
-    const int l = e / Xc, k = e - l * Xc;
+  };
+  auto finish = [&](int l, int k, float4 v) {
     const bool mirror = 2 * k > Xc;
     const int kk = mirror ? Xc - k : k;
     float2 A = make_float2(v.x, v.y), B = make_float2(v.z, v.w);
@@ -113,15 +121,34 @@ __global__ __launch_bounds__(1024) void k_rows_c2r(const float2* __restrict__ in
     if (kk == 0 || 2 * kk == Xc) { A.y = 0.f; B.y = 0.f; }   // Re of the inverse ignores them
     if (mirror) { A.y = -A.y; B.y = -B.y; }
     return make_float2(A.x - B.y, A.y + B.x);
-  }, slot, [&] { fill_twiddles(tw, X, tid, nthr); });
-  __syncthreads();
-  fft_lines<NS, 0, false, kEmax, true>(buf, LdsLines{nl, 1, LS, false, -1, true}, plan, tw, 1.f, tid,
-                                       nthr);
-  scatter_from_lds_map(buf, nl * Xc, tid, nthr, slot, [&](int e, float2 v) {
-    const int l = e / Xc, i = e - l * Xc;
+  };
+  auto store = [&](int l, int i, float2 v) {
     out[rout[2 * l] * X + i] = v.x * scale;
     if (rout[2 * l + 1] >= 0) out[rout[2 * l + 1] * X + i] = v.y * scale;
-  });
+  };
+  if constexpr (NS > 0) {
+    // first pass straight from memory, last pass straight to memory
+    constexpr int NP = StaticPlan<NS>::passes();
+    first_pass_in2<NS, 0, false, kEmax, true, false>(buf, nl, 1, LS, -1, 1.f, tid, nthr, load, finish,
+                                                     [&] { fill_twiddles(tw, X, tid, nthr); });
+    static_passes<NS, 0, false, kEmax, true, false, 1, NP - 1>(buf, nl, 1, LS, -1, tw, 1.f, tid, nthr);
+    last_pass_out<NS, 0, false, kEmax, true, false>(buf, nl, 1, LS, -1, tw, 1.f, tid, nthr, store);
+  } else {
+    gather2_to_lds(buf, nl * Xc, tid, nthr, [&](int e) {
+      const int l = e / Xc;
+      return load(l, e - l * Xc);
+    }, [&](int e, float4 v) {
+      const int l = e / Xc;
+      return finish(l, e - l * Xc, v);
+    }, slot, [&] { fill_twiddles(tw, X, tid, nthr); });
+    __syncthreads();
+    fft_lines<NS, 0, false, kEmax, true>(buf, LdsLines{nl, 1, LS, false, -1, true}, plan, tw, 1.f, tid,
+                                         nthr);
+    scatter_from_lds_map(buf, nl * Xc, tid, nthr, slot, [&](int e, float2 v) {
+      const int l = e / Xc;
+      store(l, e - l * Xc, v);
+    });
+  }
 }
 
 static int lines_per_wg_for(int X) {
@@ -487,7 +514,19 @@ __global__ __launch_bounds__(1024) void k_zop(float2* __restrict__ spec,
       }
     }
   }
-  {
+  // LDS holds [z][ch][w]: line l = ch W + w, element z at z CH W
+  if constexpr (NS > 0) {
+    // first pass of the forward Z transform straight from memory
+    first_pass_in<NS, 0, true, kEmax, false, false>(
+        buf, cin * W, CH * W, 1, pow2_shift(cin * W), -1.f, tid, nthr,
+        [&](int l, int z) {
+          const int ch = l >> wsh, w = l & (W - 1);
+          return w < weff ? sp[((long)ch * Z + z) * M + m0 + w] : make_float2(0.f, 0.f);
+        },
+        [&] { fill_twiddles(tw, Z, tid, nthr); });
+    static_passes<NS, 0, true, kEmax, false, false, 1, StaticPlan<NS>::passes()>(
+        buf, cin * W, CH * W, 1, pow2_shift(cin * W), tw, -1.f, tid, nthr);
+  } else {
     // element e = (ch, z, w) of the global tile goes to LDS [z][ch][w]
     float2 t[kEmax];
 #pragma unroll
@@ -509,10 +548,10 @@ __global__ __launch_bounds__(1024) void k_zop(float2* __restrict__ spec,
         buf[(z * CH + ch) * W + w] = t[i];
       }
     }
+    __syncthreads();
+    fft_lines<NS, 0, true>(buf, LdsLines{cin * W, CH * W, 1, true, pow2_shift(cin * W)}, plan, tw, -1.f,
+                           tid, nthr);
   }
-  __syncthreads();
-  fft_lines<NS, 0, true>(buf, LdsLines{cin * W, CH * W, 1, true, pow2_shift(cin * W)}, plan, tw, -1.f,
-                         tid, nthr);
   if (prefetch) {
 #pragma unroll
     for (int i = 0; i < kTfPrefetch; ++i) {
@@ -539,9 +578,19 @@ __global__ __launch_bounds__(1024) void k_zop(float2* __restrict__ spec,
     }
   }
   __syncthreads();
-  fft_lines<NS, 0, true>(buf, LdsLines{cout * W, CH * W, 1, true, pow2_shift(cout * W)}, plan, tw, 1.f,
-                         tid, nthr);
-  {
+  if constexpr (NS > 0) {
+    // last pass of the inverse Z transform straight to memory
+    static_passes<NS, 0, true, kEmax, false, false, 0, StaticPlan<NS>::passes() - 1>(
+        buf, cout * W, CH * W, 1, pow2_shift(cout * W), tw, 1.f, tid, nthr);
+    last_pass_out<NS, 0, true, kEmax, false, false>(
+        buf, cout * W, CH * W, 1, pow2_shift(cout * W), tw, 1.f, tid, nthr,
+        [&](int l, int z, float2 v) {
+          const int ch = l >> wsh, w = l & (W - 1);
+          if (w < weff) sp[((long)ch * Z + z) * M + m0 + w] = v;
+        });
+  } else {
+    fft_lines<NS, 0, true>(buf, LdsLines{cout * W, CH * W, 1, true, pow2_shift(cout * W)}, plan, tw, 1.f,
+                           tid, nthr);
     float2 t[kEmax];
 #pragma unroll
     for (int i = 0; i < kEmax; ++i) {

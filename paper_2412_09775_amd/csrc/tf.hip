@@ -401,28 +401,22 @@ __global__ __launch_bounds__(1024) void k_tf_rows_lf(const double* __restrict__ 
   const int PS = pad_shift(X);   // row padding
   const int LS = row_stride(X);      // padded line pitch in LDS
   // line 2r holds a, line 2r + 1 holds b of row r
-  gather_to_lds_map(buf, nr * 2 * X, tid, nthr, [&](int e) {
-    const int i = e % X;
-    const int t = e / X;
-    const int f = t & 1, r = t >> 1;
-    const float2* src = f ? b_src : a_src;
-    return src[(row0 + r) * X + i];
-  }, [&](int e) {
-    const int t = e / X;
-    return t * LS + row_slot(e - t * X, PS);
-  }, [&] { wave0_sum(partials + patch * tiles_x, tiles_x, &ibg_s); });   // sum S P^2
-  __syncthreads();
-  const float cs = (float)(1.0 / ((double)X * (double)Y * ibg_s));
+  auto load = [&](int t, int i) { return ((t & 1) ? b_src : a_src)[(row0 + (t >> 1)) * X + i]; };
   if constexpr (NS > 0) {
-    // Inverse transforms of a and b in reversed radix order up to their last
-    // pass; that pass, the product c = b conj(a) / (X Y I_bg) and the first
-    // pass of the forward transform of c run in registers (the outputs of the
-    // one are the inputs of the other, k + i NB); c goes to line 2r.
+    // Inverse transforms of a and b in reversed radix order, the first pass
+    // straight from memory; their last pass, the product c = b conj(a) /
+    // (X Y I_bg) and the first pass of the forward transform of c run in
+    // registers (the outputs of the one are the inputs of the other,
+    // k + i NB); c goes to line 2r.
     constexpr int NP = StaticPlan<NS>::passes();
     constexpr int R0 = StaticPlan<NS>::radix(0);
     constexpr int NB = NS / R0;
     constexpr int BPF = (kEmax + 2 * R0 - 1) / (2 * R0);   // butterflies of a thread
-    static_passes<NS, 0, false, kEmax, true, true, 0, NP - 1>(buf, 2 * nr, 1, LS, -1, tw, 1.f, tid,
+    first_pass_in<NS, 0, false, kEmax, true, true>(
+        buf, 2 * nr, 1, LS, -1, 1.f, tid, nthr, load,
+        [&] { wave0_sum(partials + patch * tiles_x, tiles_x, &ibg_s); });   // sum S P^2
+    const float cs = (float)(1.0 / ((double)X * (double)Y * ibg_s));
+    static_passes<NS, 0, false, kEmax, true, true, 1, NP - 1>(buf, 2 * nr, 1, LS, -1, tw, 1.f, tid,
                                                               nthr);
     float2 cv[BPF][R0];
     int cr[BPF], ck[BPF];
@@ -471,6 +465,15 @@ __global__ __launch_bounds__(1024) void k_tf_rows_lf(const double* __restrict__ 
     __syncthreads();
     static_passes<NS, 0, false, kEmax, true, false, 1, NP>(buf, nr, 1, 2 * LS, -1, tw, -1.f, tid, nthr);
   } else {
+    gather_to_lds_map(buf, nr * 2 * X, tid, nthr, [&](int e) {
+      const int t = e / X;
+      return load(t, e - t * X);
+    }, [&](int e) {
+      const int t = e / X;
+      return t * LS + row_slot(e - t * X, PS);
+    }, [&] { wave0_sum(partials + patch * tiles_x, tiles_x, &ibg_s); });   // sum S P^2
+    __syncthreads();
+    const float cs = (float)(1.0 / ((double)X * (double)Y * ibg_s));
     fft_lines<NS, 0, false, kEmax, true>(buf, LdsLines{2 * nr, 1, LS, false, -1, true}, plan, tw, 1.f,
                                          tid, nthr);
     for (int e = tid; e < nr * X; e += nthr) {
