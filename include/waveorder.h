@@ -269,8 +269,10 @@ int wo_stitch_tiles(const float* tiles, int32_t ny_t, int32_t nx_t, int32_t P, i
 /* Runs one call -- op WO_OP_TRANSFER_FUNCTION (writes `out` as tf_out),
  * WO_OP_FORWARD (in = f, out = d), WO_OP_RECONSTRUCT (in = d, out = f, eta)
  * or WO_OP_ADJOINT (in = r, out = g), arguments as for that call, b = NULL --
- * while recording its tunable passes, then times every candidate schedule of
- * each pass `reps` times on the call's own buffers and stores the fastest.
+ * while recording its tunable passes; then, pass by pass, times the whole
+ * call `reps` times with every candidate schedule of that pass (the other
+ * passes keeping their current schedules) and stores the one with the
+ * fastest single call.
  * On return `out` and `ws` hold unspecified values (run the call again);
  * tf and in are only read.  Synchronises `stream`. */
 int wo_fft_tune(int32_t op, const wo_optics* o, int32_t n, const void* tf, const float* in, float* out,
