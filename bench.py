@@ -288,6 +288,20 @@ def main():
         for _ in range(args.warmup):
             full_step()
         torch.cuda.synchronize()
+        # The tuner judges each call on its own; the step runs the two calls
+        # back to back (other cache contents), so keep its table only if the
+        # step is faster with it.
+        a = time.perf_counter()
+        for _ in range(args.steps):
+            full_step()
+        torch.cuda.synchronize()
+        tuner["ms_per_step_tuned_schedules"] = (time.perf_counter() - a) * 1e3 / args.steps
+        if tuner["ms_per_step_tuned_schedules"] >= tuner["ms_per_step_default_schedules"]:
+            tuner["tuned_table_dropped"] = api.fft_plans_export().splitlines()
+            api.fft_plans_clear()
+            for _ in range(args.warmup):
+                full_step()
+            torch.cuda.synchronize()
     if args.save_fft_plans:
         os.makedirs(os.path.dirname(os.path.abspath(args.save_fft_plans)), exist_ok=True)
         with open(args.save_fft_plans, "w") as fh:
@@ -295,7 +309,19 @@ def main():
     tuner["table"] = api.fft_plans_export().splitlines()
     print(f"[bench] fft schedules: {tuner}", file=sys.stderr, flush=True)
 
-    # ---- timed region: K whole steps, with per-kernel HIP events on the library's stream
+    # ---- per-kernel pass: K steps with every library kernel bracketed by HIP events
+    # (the events add gaps between launches, so this pass is not the timed one)
+    api.timing_enable(True)
+    for _ in range(args.steps):
+        full_step()
+    torch.cuda.synchronize()
+    api.timing_enable(False)
+    kern = api.timing_report()
+    dom = max(kern, key=lambda k: kern[k][1])
+
+    # ---- timed region: K whole steps; HIP events on the library's stream around
+    # the dominant kernel only (its duration for the roofline)
+    api.timing_select(dom)
     api.timing_enable(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -304,7 +330,8 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     api.timing_enable(False)
-    kern = api.timing_report()
+    dom_rec = api.timing_report()[dom]
+    api.timing_select(None)
     ms = (t1 - t0) * 1e3 / args.steps
     value = V / (ms * 1e-3)
 
@@ -325,9 +352,8 @@ def main():
             ent["alg_bytes"] = b
             ent["alg_GBps"] = round(b / (per * 1e-3) / 1e9, 1)
         kernels[name] = ent
-    dom = max(kern, key=lambda k: kern[k][1])
     dom_b = kernel_bytes(dom, Z, Y, X) or 0
-    dom_ms = kern[dom][1] / kern[dom][0]
+    dom_ms = dom_rec[1] / dom_rec[0]
     ach = dom_b / (dom_ms * 1e-3) / 1e9
     roof = {"kernel": dom, "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": measured_traffic(dom),

@@ -358,6 +358,9 @@ int wo_crop_stacks(const float* in, int32_t n, int32_t nz, int32_t ny, int32_t n
  * failed. */
 int wo_timing_enable(int on);
 int wo_timing_report(char* buf, size_t len);
+/* Restricts the events to launches of one kernel name (as reported); NULL or
+ * "" selects every kernel again.  The name is copied. */
+int wo_timing_select(const char* name);
 
 /* Human-readable message for a status code. */
 const char* wo_strerror(int status);

@@ -38,7 +38,7 @@ SYMBOLS = ("wo_bank_shape", "wo_workspace_size", "wo_transfer_function", "wo_for
            "wo_cnn_train_step", "wo_conv3d_forward", "wo_conv3d_input_grad", "wo_conv3d_weight_grad",
            "wo_synth_thin_cells", "wo_add_gaussian_noise", "wo_crop_stacks", "wo_fft_tune",
            "wo_fft_plans_export", "wo_fft_plans_import", "wo_fft_plans_clear", "wo_fft_candidates",
-           "wo_tile_grid", "wo_stitch_tiles")
+           "wo_tile_grid", "wo_stitch_tiles", "wo_timing_select")
 
 _FIELDS = ("model", "nz", "ny", "nx", "dz", "dy", "dx", "wavelength", "na_ill", "na_det",
            "n_medium", "defocus", "tilt_zenith", "tilt_azimuth", "edge_width", "swing")
@@ -143,6 +143,7 @@ def load(path: str = LIB_PATH):
     lib.wo_crop_stacks.argtypes = [vp, i32, i32, i32, i32, vp, i32, i32, i32, i32, i32, i32, vp, vp]
     lib.wo_timing_enable.argtypes = [ctypes.c_int]
     lib.wo_timing_report.argtypes = [ctypes.c_char_p, ctypes.c_size_t]
+    lib.wo_timing_select.argtypes = [ctypes.c_char_p]
     for name in SYMBOLS:
         getattr(lib, name)
     _lib = lib
@@ -278,6 +279,11 @@ def adjoint(optics, tf, r, ws=None, stream=None):
 def timing_enable(on: bool = True):
     """Bracket every library kernel launch with HIP events (instrumentation)."""
     load().wo_timing_enable(1 if on else 0)
+
+
+def timing_select(name=None):
+    """Restrict the timing events to one kernel name (None: every kernel)."""
+    _check(load().wo_timing_select(name.encode() if name else None), "wo_timing_select")
 
 
 def timing_report() -> dict:

@@ -40,6 +40,7 @@ struct TimingRec {
 };
 std::mutex g_tmu;
 bool g_timing = false;
+std::string g_tsel;   // kernel name the events are restricted to (empty: all)
 std::vector<TimingRec> g_recs;
 std::vector<hipEvent_t> g_pool;
 
@@ -59,6 +60,10 @@ bool timing_enabled() { return g_timing; }
 
 void timing_begin(const char* name, hipStream_t s, void** token) {
   std::lock_guard<std::mutex> lk(g_tmu);
+  if (!g_tsel.empty() && g_tsel != name) {
+    *token = nullptr;
+    return;
+  }
   TimingRec* r = new TimingRec{name, take_event(), take_event()};
   if (!r->a || !r->b) {
     delete r;
@@ -836,6 +841,12 @@ int wo_version(void) { return 100; }
 int wo_timing_enable(int on) {
   std::lock_guard<std::mutex> lk(wo::g_tmu);
   wo::g_timing = on != 0;
+  return WO_OK;
+}
+
+int wo_timing_select(const char* name) {
+  std::lock_guard<std::mutex> lk(wo::g_tmu);
+  wo::g_tsel = name ? name : "";
   return WO_OK;
 }
 
