@@ -107,6 +107,15 @@ typedef struct wo_optics {
   double edge_width;       /* pupil edge: 0 = hard disc (boundary included); w > 0 =
                               C1 smoothstep of half-width w lateral frequency pixels */
   double swing;            /* POL5_3D only: retarder swing in waves */
+  double zernike[7];       /* detection aberration, waves, on Zernike polynomials
+                              Noll j = 5..11 (astigmatism 5, 6; coma 7, 8; trefoil
+                              9, 10; primary spherical 11), unit-RMS (Noll)
+                              normalisation over the pupil radius NA_det/lambda0:
+                              the detection pupil becomes P(p) exp(i 2 pi W(p)),
+                              W = sum_j zernike[j-5] Z_j(rho, phi), rho = |p| /
+                              (NA_det/lambda0), phi = atan2(p_y, p_x) (Methods,
+                              detection-parameter branch: Zernike coefficients in
+                              calc_det_pupil).  Zero: no aberration. */
 } wo_optics;
 
 /* Bank shape of the model: *C channels, *P properties, *dims spatial
@@ -159,7 +168,9 @@ int wo_adjoint(const wo_optics* o, int32_t n, const void* tf, const float* r, fl
  * Tikhonov phase reconstruction.  Gradients are hand-written reverse mode
  * through the solve and the transfer-function synthesis; the transfer
  * function is recomputed every iteration.  Soft pupil edges (edge_width > 0)
- * are needed for non-zero NA and tilt gradients. */
+ * are needed for non-zero NA and tilt gradients.  Aberrated optics (any
+ * zernike coefficient non-zero) are not accepted here (WO_EUNSUPPORTED): the
+ * gradient has no aberration terms. */
 
 /* Unlike the calls above, the calls of this section accept patches of uneven
  * shapes (each o[i] its own nz >= 2, ny and nx <= 2048, dz, dy, dx): the stacks are

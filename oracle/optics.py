@@ -24,6 +24,13 @@ R6  Pupil edge: hard disc with the boundary included, or a compact C1
 R7  Tilt shifts the source disc to q0 = (n sin(zenith)/lambda0) (cos az,
     sin az); the tilted disc must stay inside k_m.
 R8  Defocus shifts every plane, z -> z - defocus.
+R18 Detection aberrations (Ext. Data Fig. 3b: Zernike coefficients enter
+    calc_det_pupil): the detection pupil becomes P(p) exp(i 2 pi W(p)), W in
+    waves, W = sum_j c_j Z_j(rho, phi) over Noll's unit-RMS Zernike
+    polynomials j = 5..11, rho = |p| / (NA_det / lambda0), phi = atan2(p_y,
+    p_x).  The phase multiplies the pupil wherever it appears (direct and
+    scattered arms, fluorescence); the polynomials continue past rho = 1 into
+    a soft edge.  I_bg = sum S |P|^2 is unchanged.
 All arithmetic is float64 / complex128.
 """
 
@@ -61,6 +68,7 @@ class Optics:
     tilt_azimuth: float = 0.0
     edge_width: float = 0.0    # soft pupil edge half-width in frequency pixels; 0 = hard
     swing: float = 0.1         # polarisation bank only
+    zernike: tuple = ()        # detection aberration, waves, Noll j = 5, 6, ... (R18)
 
     def replace(self, **kw) -> "Optics":
         return dataclasses.replace(self, **kw)
@@ -122,6 +130,57 @@ def detection_pupil(o: Optics) -> np.ndarray:
     """P(p): disc of radius NA_det/lambda0 (Ext. Data Fig. 3b, calc_det_pupil)."""
     fy, fx = lateral_frequencies(o)
     return radius_disc(fy, fx, o.na_det / o.wavelength, o.edge_width * o.dnu)
+
+
+ZERNIKE_FIRST = 5     # Noll index of zernike[0]
+
+
+def noll_nm(j: int):
+    """(n, m) of Noll's index j >= 1: radial order n, azimuthal order m >= 0.
+    Within order n the indices run through |m| ascending, each m > 0 twice."""
+    n = 0
+    while (n + 1) * (n + 2) // 2 < j:
+        n += 1
+    k = j - n * (n + 1) // 2 - 1
+    ms = [m for m in range(n % 2, n + 1, 2) for _ in range(1 if m == 0 else 2)]
+    return n, ms[k]
+
+
+def zernike_noll(j: int, rho, phi):
+    """Noll's Zernike polynomial Z_j: unit RMS over the unit disc, sqrt(n + 1)
+    R_n^0 for m = 0, else sqrt(2 (n + 1)) R_n^m times cos(m phi) (even j) or
+    sin(m phi) (odd j); R_n^m(rho) = sum_s (-1)^s (n - s)! / (s! ((n + m)/2 - s)!
+    ((n - m)/2 - s)!) rho^(n - 2s)."""
+    n, m = noll_nm(j)
+    rho = np.asarray(rho, dtype=np.float64)
+    R = np.zeros_like(rho)
+    for s_ in range((n - m) // 2 + 1):
+        c = ((-1) ** s_ * math.factorial(n - s_)
+             / (math.factorial(s_) * math.factorial((n + m) // 2 - s_) * math.factorial((n - m) // 2 - s_)))
+        R = R + c * rho ** (n - 2 * s_)
+    if m == 0:
+        return math.sqrt(n + 1) * R
+    ang = np.cos(m * np.asarray(phi)) if j % 2 == 0 else np.sin(m * np.asarray(phi))
+    return math.sqrt(2 * (n + 1)) * R * ang
+
+
+def aberration_waves(o: Optics) -> np.ndarray:
+    """W(p) in waves on the lateral grid (R18); zeros without coefficients."""
+    fy, fx = lateral_frequencies(o)
+    W = np.zeros_like(fy)
+    if not any(o.zernike):
+        return W
+    rho = np.sqrt(fy * fy + fx * fx) / (o.na_det / o.wavelength)
+    phi = np.arctan2(fy, fx)
+    for k, c in enumerate(o.zernike):
+        if c:
+            W = W + c * zernike_noll(ZERNIKE_FIRST + k, rho, phi)
+    return W
+
+
+def aberration(o: Optics) -> np.ndarray:
+    """exp(i 2 pi W(p)): the phase factor of the aberrated detection pupil (R18)."""
+    return np.exp(2j * np.pi * aberration_waves(o))
 
 
 def source_centre(o: Optics):

@@ -45,6 +45,7 @@ def labelfree_point_response(o: op.Optics, S: np.ndarray | None = None) -> np.nd
     if S is None:
         S = op.illumination_pupil(o)
     P = op.detection_pupil(o)
+    E = op.aberration(o)       # detection aberration phase (R18)
     g = op.greens_spectrum(o)
     ibg = float(np.sum(S * P * P))
     if ibg <= 0:
@@ -52,8 +53,8 @@ def labelfree_point_response(o: op.Optics, S: np.ndarray | None = None) -> np.nd
     out = np.empty((o.nz, o.ny, o.nx), dtype=np.complex128)
     for k, z in enumerate(_planes(o)):
         prop = op.propagator(o, z)
-        a = sfft.ifft2(S * P * prop)
-        b = sfft.ifft2(P * g * prop)
+        a = sfft.ifft2(S * P * E * prop)
+        b = sfft.ifft2(P * E * g * prop)
         out[k] = (o.ny * o.nx / ibg) * b * np.conj(a)
     return out
 
@@ -76,7 +77,7 @@ def labelfree_thin(o: op.Optics) -> np.ndarray:
 
 def fluorescence_3d(o: op.Optics) -> np.ndarray:
     """Scalar fluorescence OTF [P * P]: (Z, Y, X) complex, H(0) = 1 (Table 1)."""
-    P = op.detection_pupil(o)
+    P = op.detection_pupil(o) * op.aberration(o)
     psf = np.empty((o.nz, o.ny, o.nx))
     for k, z in enumerate(op.z_planes_3d(o)):
         h = sfft.ifft2(P * op.propagator(o, z))
@@ -203,17 +204,20 @@ def labelfree_response_at(o: op.Optics, ky: int, kx: int) -> np.ndarray:
 
         C_z(nu) = sum_q S(q) P(q) P(q + nu) g(q + nu) e^{i 2 pi (kz(q + nu) - kz(q)) (z - dz0)} / I_bg
 
+    (times conj(E(q)) E(q + nu) with the aberration phase E of R18).
+
     Independent of any FFT; used to check full-size banks frequency by frequency.
     Returns (Z,) complex.
     """
     S = op.illumination_pupil(o)
     P = op.detection_pupil(o)
+    E = op.aberration(o)
     g = op.greens_spectrum(o)
     kzz = op.axial_wavenumber(o)
     ibg = float(np.sum(S * P * P))
     qy, qx = np.nonzero(S * P)
     py, px = (qy + ky) % o.ny, (qx + kx) % o.nx        # q + nu on the periodic grid
-    w = S[qy, qx] * P[qy, qx] * P[py, px] * g[py, px]
+    w = S[qy, qx] * P[qy, qx] * np.conj(E[qy, qx]) * P[py, px] * E[py, px] * g[py, px]
     dk = kzz[py, px] - kzz[qy, qx]
     zs = _planes(o) - o.defocus
     return np.exp(2j * np.pi * np.outer(zs, dk)) @ w / ibg

@@ -44,9 +44,13 @@ _FIELDS = ("model", "nz", "ny", "nx", "dz", "dy", "dx", "wavelength", "na_ill", 
            "n_medium", "defocus", "tilt_zenith", "tilt_azimuth", "edge_width", "swing")
 
 
+N_ZERNIKE = 7   # Noll j = 5..11
+
+
 class WoOptics(ctypes.Structure):
-    _fields_ = [("model", ctypes.c_int32), ("nz", ctypes.c_int32), ("ny", ctypes.c_int32),
-                ("nx", ctypes.c_int32)] + [(f, ctypes.c_double) for f in _FIELDS[4:]]
+    _fields_ = ([("model", ctypes.c_int32), ("nz", ctypes.c_int32), ("ny", ctypes.c_int32),
+                 ("nx", ctypes.c_int32)] + [(f, ctypes.c_double) for f in _FIELDS[4:]]
+                + [("zernike", ctypes.c_double * N_ZERNIKE)])
 
 
 @dataclasses.dataclass
@@ -69,6 +73,7 @@ class Optics:
     tilt_azimuth: float = 0.0
     edge_width: float = 0.0
     swing: float = 0.1
+    zernike: tuple = ()   # detection aberration, waves, Noll j = 5..11 (up to 7 values)
 
 
 class WoAutotuneOpts(ctypes.Structure):
@@ -162,6 +167,14 @@ def optics_array(optics) -> ctypes.Array:
     for i, o in enumerate(optics):
         for f in _FIELDS:
             setattr(arr[i], f, int(_get(o, f)) if f in ("model", "nz", "ny", "nx") else float(_get(o, f)))
+        z = getattr(o, "zernike", None)
+        if z is None and isinstance(o, dict):
+            z = o.get("zernike")
+        z = tuple(z) if z is not None else ()
+        if len(z) > N_ZERNIKE:
+            raise ValueError(f"at most {N_ZERNIKE} Zernike coefficients (Noll 5..11)")
+        for j in range(N_ZERNIKE):
+            arr[i].zernike[j] = float(z[j]) if j < len(z) else 0.0
     return arr
 
 

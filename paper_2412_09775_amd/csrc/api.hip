@@ -163,7 +163,15 @@ int check_optics(const wo_optics* o) {
   if (lat >= nyq) return WO_EALIAS;
   if (o->model != WO_MODEL_LABELFREE_THIN && ax >= 0.5 / o->dz) return WO_EALIAS;
   if (o->model == WO_MODEL_POL5_3D && !(isfinite(o->swing))) return WO_EINVAL;
+  for (int j = 0; j < 7; ++j)
+    if (!isfinite(o->zernike[j])) return WO_EINVAL;
   return WO_OK;
+}
+
+bool aberrated(const wo_optics& o) {
+  for (int j = 0; j < 7; ++j)
+    if (o.zernike[j] != 0.0) return true;
+  return false;
 }
 
 // Every aperture of the 9-aperture model must pass direct light (sum_q S_c P^2 > 0),
@@ -443,6 +451,7 @@ DevOptics dev_optics(const wo_optics& o) {
   d.tilt_zenith = o.tilt_zenith;
   d.tilt_azimuth = o.tilt_azimuth;
   d.edge_width = o.edge_width;
+  for (int j = 0; j < 7; ++j) d.zern[j] = (float)o.zernike[j];
   return d;
 }
 
@@ -518,6 +527,7 @@ int validate_thin(const wo_optics* o, int32_t n) {
     if (st) return st;
     if (o[i].model != WO_MODEL_LABELFREE_THIN || o[i].nz < 2 || o[i].ny > 2048 || o[i].nx > 2048)
       return WO_EUNSUPPORTED;
+    if (aberrated(o[i])) return WO_EUNSUPPORTED;   // the gradient has no aberration terms
     st = check_optics(&o[i]);
     if (st) return st;
   }

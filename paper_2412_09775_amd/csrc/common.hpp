@@ -432,9 +432,27 @@ struct DevOptics {
   double kappa[5][4][2];   // polarisation coupling (re, im), pol5 only
   double ibg;
   int sector;              // illumination aperture: -1 the full disc, 0..7 an azimuthal sector
-  int ipad;
-  double pad[2];
+  float zern[7];           // detection aberration, waves, Noll j = 5..11
 };
+
+// Detection aberration W(p) in waves: sum of zern[j - 5] Z_j over Noll's
+// unit-RMS Zernike polynomials j = 5..11 at rho = |p| / (NA_det / lambda0),
+// with cos(m phi), sin(m phi) formed from p / |p| (phi = atan2(p_y, p_x)).
+__host__ __device__ inline double aberration_waves(const DevOptics& o, double fy, double fx) {
+  bool any = false;
+  for (int j = 0; j < 7; ++j) any |= o.zern[j] != 0.f;
+  if (!any) return 0.0;
+  const double pr = sqrt(fy * fy + fx * fx);
+  const double r = pr / (o.na_det / o.wavelength), r2 = r * r, r3 = r2 * r;
+  const double s1 = pr > 0.0 ? fy / pr : 0.0, c1 = pr > 0.0 ? fx / pr : 1.0;
+  const double s2 = 2.0 * s1 * c1, c2 = c1 * c1 - s1 * s1;            // sin, cos of 2 phi
+  const double s3 = s2 * c1 + c2 * s1, c3 = c2 * c1 - s2 * s1;        // sin, cos of 3 phi
+  const double k6 = 2.449489742783178, k8 = 2.8284271247461903, k5 = 2.23606797749979;
+  const double coma = k8 * (3.0 * r3 - 2.0 * r);
+  return o.zern[0] * k6 * r2 * s2 + o.zern[1] * k6 * r2 * c2 + o.zern[2] * coma * s1 +
+         o.zern[3] * coma * c1 + o.zern[4] * k8 * r3 * s3 + o.zern[5] * k8 * r3 * c3 +
+         o.zern[6] * k5 * (6.0 * r2 * r2 - 6.0 * r2 + 1.0);
+}
 
 // Azimuthal sector k of the direction (dy, dx): the azimuth, from +x towards +y,
 // lies in [k pi/4, (k+1) pi/4); the origin is in sector 0.  Comparisons only.

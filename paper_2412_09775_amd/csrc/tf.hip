@@ -124,7 +124,7 @@ __global__ __launch_bounds__(1024) void k_tf_fields_y(const DevOptics* __restric
     constexpr int B0 = (kEmax + R0 - 1) / R0, BL = (kEmax + RL - 1) / RL;
     static_assert(NP >= 2, "compiled lateral lengths have at least two passes");
     double tkz[B0][R0];
-    float fac[B0][R0];
+    float fac[B0][R0], ab2[B0][R0];   // ab2: 2 W(p), the aberration phase in units of pi
     {
       const double hw = soft_halfwidth(o, sm);
       const double km = o.n_medium / o.wavelength;
@@ -141,6 +141,7 @@ __global__ __launch_bounds__(1024) void k_tf_fields_y(const DevOptics* __restric
         for (int r = 0; r < R0; ++r) {
           tkz[b][r] = 0.0;
           fac[b][r] = 0.f;
+          ab2[b][r] = 0.f;
           if (j < nl * NB0 && kx < X) {
             const int ky = k + r * NB0;
             const double fy = fftfreq(ky, Y, sm.dy), fx = fftfreq(kx, X, sm.dx);
@@ -148,6 +149,7 @@ __global__ __launch_bounds__(1024) void k_tf_fields_y(const DevOptics* __restric
             if (P != 0.0) {
               const double kz = sqrt(fmax(km * km - (fy * fy + fx * fx), 0.0));
               tkz[b][r] = 2.0 * kz;
+              ab2[b][r] = (float)(2.0 * aberration_waves(o, fy, fx));
               if (fluor) {
                 fac[b][r] = (float)P;
                 psum += P * P;
@@ -186,7 +188,7 @@ __global__ __launch_bounds__(1024) void k_tf_fields_y(const DevOptics* __restric
             if (fac[b][r] != 0.f) {
               // phase 2 pi kz (z - dz0): reduce the argument (in units of pi) in
               // FP64 to [-1, 1], then evaluate sin/cos in FP32
-              const double arg = tkz[b][r] * dzr;
+              const double arg = tkz[b][r] * dzr + (double)ab2[b][r];
               const float rr = (float)(arg - 2.0 * rint(0.5 * arg));
               float sn, cs;
               sincospif(rr, &sn, &cs);
@@ -230,6 +232,7 @@ __global__ __launch_bounds__(1024) void k_tf_fields_y(const DevOptics* __restric
   } else {
     // z-independent factors of this thread's elements e = tid + i * nthr
     double tkz[EPT], sp[EPT], gg[fluor ? 1 : EPT];
+    float ab2[EPT];   // 2 W(p): the aberration phase in units of pi
     {
       const double hw = soft_halfwidth(o, sm);
       const double km = o.n_medium / o.wavelength;
@@ -241,6 +244,7 @@ __global__ __launch_bounds__(1024) void k_tf_fields_y(const DevOptics* __restric
       for (int i = 0; i < EPT; ++i) {
         tkz[i] = 0.0;
         sp[i] = 0.0;
+        ab2[i] = 0.f;
         if (!fluor) gg[i] = 0.0;
         const int e = tid + i * nthr;
         if (e < Y * W) {
@@ -252,6 +256,7 @@ __global__ __launch_bounds__(1024) void k_tf_fields_y(const DevOptics* __restric
             if (P != 0.0) {
               const double kz = sqrt(fmax(km * km - (fy * fy + fx * fx), 0.0));
               tkz[i] = 2.0 * kz;
+              ab2[i] = (float)(2.0 * aberration_waves(o, fy, fx));
               if (fluor) {
                 sp[i] = P;
                 psum += P * P;
@@ -283,7 +288,7 @@ __global__ __launch_bounds__(1024) void k_tf_fields_y(const DevOptics* __restric
           if (sp[i] != 0.0 || (!fluor && gg[i] != 0.0)) {
             // phase 2 pi kz (z - dz0): reduce the argument (in units of pi) in FP64
             // to [-1, 1], then evaluate sin/cos in FP32
-            const double arg = tkz[i] * dzr;
+            const double arg = tkz[i] * dzr + (double)ab2[i];
             const float rr = (float)(arg - 2.0 * rint(0.5 * arg));
             float snf, csf;
             sincospif(rr, &snf, &csf);

@@ -90,6 +90,14 @@ CASES = {
                                           tilt_azimuth=0.5, edge_width=0.5),
                                   sectors(nz=12, ny=48, nx=40, na_det=1.1, tilt_zenith=0.05,
                                           edge_width=0.5)],
+    # detection aberrations (Noll 5..11, waves): every model, compiled and runtime lengths
+    "labelfree_3d_aberrated": [labelfree(zernike=(0.15, -0.1, 0.08, 0.05, -0.04, 0.03, 0.12),
+                                         tilt_zenith=0.2, edge_width=0.5)],
+    "labelfree_aberrated_runtime": [labelfree(nz=9, ny=40, nx=50, zernike=(0.1,) * 7)],
+    "fluor_aberrated": [fluor(zernike=(0.1, 0.0, 0.0, 0.2, 0.0, 0.0, -0.15), defocus=0.2)],
+    "thin_aberrated_batch2": [thin(zernike=(0.1,)), thin(zernike=(0.0,) * 6 + (0.2,), defocus=0.5)],
+    "pol5_aberrated": [pol5(zernike=(0.0, 0.0, 0.1))],
+    "sectors9_aberrated": [sectors(zernike=(0.05, 0.05, 0.1))],
 }
 
 

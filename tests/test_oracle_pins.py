@@ -223,6 +223,7 @@ def abbe_point_response(o, S=None):
     if S is None:
         S = op.illumination_pupil(o)
     P = op.detection_pupil(o)
+    E = op.aberration(o)            # detection aberration phase on the pupil (1 without)
     fy, fx = op.lateral_frequencies(o)
     kz = op.axial_wavenumber(o)
     km = o.k_medium
@@ -238,7 +239,9 @@ def abbe_point_response(o, S=None):
             acc = np.zeros((o.ny, o.nx), dtype=np.complex128)
             for pi in pidx:
                 p = tuple(pi)
-                amp = S[q] * P[q] * P[p] * (1j * km / kz[p])
+                # direct plane wave q through the aberrated pupil (conjugated in
+                # b conj(a)), scattered plane wave p through it
+                amp = S[q] * P[q] * np.conj(E[q]) * P[p] * E[p] * (1j * km / kz[p])
                 ph = (fy[p] - fy[q]) * ys + (fx[p] - fx[q]) * xs + (kz[p] - kz[q]) * (z - o.defocus)
                 acc += amp * np.exp(2j * np.pi * ph)
             out[zi] += acc
@@ -246,7 +249,8 @@ def abbe_point_response(o, S=None):
 
 
 @pytest.mark.parametrize("kw", [dict(), dict(defocus=0.3, tilt_zenith=0.2, tilt_azimuth=0.7),
-                                dict(model=op.LABELFREE_THIN, nz=3, defocus=-0.2, edge_width=0.5)])
+                                dict(model=op.LABELFREE_THIN, nz=3, defocus=-0.2, edge_width=0.5),
+                                dict(defocus=0.1, tilt_zenith=0.1, zernike=(0.2, -0.1, 0.15, 0.0, 0.1, 0, 0.2))])
 def test_labelfree_point_response_is_abbe_source_sum(kw):
     """Label-free contrast summed over source points (unified-framework section)."""
     o = lf_optics(ny=8, nx=8, dx=0.13, dy=0.13, na_det=0.8, na_ill=0.45, **kw)
@@ -391,9 +395,10 @@ def test_hard_edges_of_test_optics_are_not_on_lattice_points():
         assert op.hard_edge_margin(o) > 1e-6
 
 
-def test_direct_frequency_sum_equals_the_bank():
+@pytest.mark.parametrize("zern", [(), (0.1, 0.0, -0.12, 0.05, 0.0, 0.08, 0.1)])
+def test_direct_frequency_sum_equals_the_bank(zern):
     """One-frequency evaluation by the direct source sum (no FFT) equals the FFT-route bank."""
-    o = lf_optics(nz=8, ny=32, nx=32, defocus=0.1, tilt_zenith=0.1, tilt_azimuth=0.4)
+    o = lf_optics(nz=8, ny=32, nx=32, defocus=0.1, tilt_zenith=0.1, tilt_azimuth=0.4, zernike=zern)
     hp, ha = tfm.labelfree_3d(o)
     for kz, ky, kx in [(0, 0, 0), (1, 2, 3), (7, 31, 5), (3, 10, 30), (4, 16, 16)]:
         a, b = tfm.labelfree_3d_at(o, kz, ky, kx)
