@@ -955,7 +955,8 @@ int wo_transfer_function(const wo_optics* o, int32_t n, void* tf_out, void* ws, 
   float2* ab = (float2*)w;
   w += align_up((size_t)nv * nf * s.Z * s.Y * s.X * sizeof(float2));
   WO_TRY(launch_set_params(dopt, h.data(), nv, hs));
-  const Sampling sm = sampling_of(o);
+  Sampling sm = sampling_of(o);
+  for (int i = 0; i < n; ++i) sm.aberrated |= aberrated(o[i]) ? 1 : 0;
   WO_TRY(launch_tf_fields_y(dopt, sm, nv, ab, partials, hs));
   float2* tf = (float2*)tf_out;
   const long M = s.Y * s.Xh;

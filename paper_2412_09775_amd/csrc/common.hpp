@@ -480,6 +480,7 @@ struct Sampling {
   int model;
   int nz, ny, nx;
   double dz, dy, dx;
+  int aberrated = 0;   // some patch has detection aberrations (selects the kernel variant)
 };
 
 __host__ __device__ __forceinline__ double fftfreq(int k, int n, double d) {

@@ -86,7 +86,7 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
 // The workgroup of the first chunk also writes the tile's share of the pupil
 // sum (sum S P^2 for label-free, sum P^2 for fluorescence) to
 // partials[patch * tiles_x + tile].
-template <int NS, int NF>
+template <int NS, int NF, bool AB>
 __global__ __launch_bounds__(1024) void k_tf_fields_y(const DevOptics* __restrict__ opt,
                                                       Sampling sm, float2* __restrict__ ab,
                                                       double* __restrict__ partials, int W,
@@ -124,7 +124,8 @@ __global__ __launch_bounds__(1024) void k_tf_fields_y(const DevOptics* __restric
     constexpr int B0 = (kEmax + R0 - 1) / R0, BL = (kEmax + RL - 1) / RL;
     static_assert(NP >= 2, "compiled lateral lengths have at least two passes");
     double tkz[B0][R0];
-    float fac[B0][R0], ab2[B0][R0];   // ab2: 2 W(p), the aberration phase in units of pi
+    float fac[B0][R0];
+    float ab2[AB ? B0 : 1][AB ? R0 : 1];   // 2 W(p): the aberration phase in units of pi
     {
       const double hw = soft_halfwidth(o, sm);
       const double km = o.n_medium / o.wavelength;
@@ -141,7 +142,7 @@ __global__ __launch_bounds__(1024) void k_tf_fields_y(const DevOptics* __restric
         for (int r = 0; r < R0; ++r) {
           tkz[b][r] = 0.0;
           fac[b][r] = 0.f;
-          ab2[b][r] = 0.f;
+          if constexpr (AB) ab2[b][r] = 0.f;
           if (j < nl * NB0 && kx < X) {
             const int ky = k + r * NB0;
             const double fy = fftfreq(ky, Y, sm.dy), fx = fftfreq(kx, X, sm.dx);
@@ -149,7 +150,7 @@ __global__ __launch_bounds__(1024) void k_tf_fields_y(const DevOptics* __restric
             if (P != 0.0) {
               const double kz = sqrt(fmax(km * km - (fy * fy + fx * fx), 0.0));
               tkz[b][r] = 2.0 * kz;
-              ab2[b][r] = (float)(2.0 * aberration_waves(o, fy, fx));
+              if constexpr (AB) ab2[b][r] = (float)(2.0 * aberration_waves(o, fy, fx));
               if (fluor) {
                 fac[b][r] = (float)P;
                 psum += P * P;
@@ -188,7 +189,8 @@ __global__ __launch_bounds__(1024) void k_tf_fields_y(const DevOptics* __restric
             if (fac[b][r] != 0.f) {
               // phase 2 pi kz (z - dz0): reduce the argument (in units of pi) in
               // FP64 to [-1, 1], then evaluate sin/cos in FP32
-              const double arg = tkz[b][r] * dzr + (double)ab2[b][r];
+              double arg = tkz[b][r] * dzr;
+              if constexpr (AB) arg += (double)ab2[b][r];
               const float rr = (float)(arg - 2.0 * rint(0.5 * arg));
               float sn, cs;
               sincospif(rr, &sn, &cs);
@@ -232,7 +234,7 @@ __global__ __launch_bounds__(1024) void k_tf_fields_y(const DevOptics* __restric
   } else {
     // z-independent factors of this thread's elements e = tid + i * nthr
     double tkz[EPT], sp[EPT], gg[fluor ? 1 : EPT];
-    float ab2[EPT];   // 2 W(p): the aberration phase in units of pi
+    float ab2[AB ? EPT : 1];   // 2 W(p): the aberration phase in units of pi
     {
       const double hw = soft_halfwidth(o, sm);
       const double km = o.n_medium / o.wavelength;
@@ -244,7 +246,7 @@ __global__ __launch_bounds__(1024) void k_tf_fields_y(const DevOptics* __restric
       for (int i = 0; i < EPT; ++i) {
         tkz[i] = 0.0;
         sp[i] = 0.0;
-        ab2[i] = 0.f;
+        if constexpr (AB) ab2[i] = 0.f;
         if (!fluor) gg[i] = 0.0;
         const int e = tid + i * nthr;
         if (e < Y * W) {
@@ -256,7 +258,7 @@ __global__ __launch_bounds__(1024) void k_tf_fields_y(const DevOptics* __restric
             if (P != 0.0) {
               const double kz = sqrt(fmax(km * km - (fy * fy + fx * fx), 0.0));
               tkz[i] = 2.0 * kz;
-              ab2[i] = (float)(2.0 * aberration_waves(o, fy, fx));
+              if constexpr (AB) ab2[i] = (float)(2.0 * aberration_waves(o, fy, fx));
               if (fluor) {
                 sp[i] = P;
                 psum += P * P;
@@ -288,7 +290,8 @@ __global__ __launch_bounds__(1024) void k_tf_fields_y(const DevOptics* __restric
           if (sp[i] != 0.0 || (!fluor && gg[i] != 0.0)) {
             // phase 2 pi kz (z - dz0): reduce the argument (in units of pi) in FP64
             // to [-1, 1], then evaluate sin/cos in FP32
-            const double arg = tkz[i] * dzr + (double)ab2[i];
+            double arg = tkz[i] * dzr;
+            if constexpr (AB) arg += (double)ab2[i];
             const float rr = (float)(arg - 2.0 * rint(0.5 * arg));
             float snf, csf;
             sincospif(rr, &snf, &csf);
@@ -351,14 +354,16 @@ hipError_t launch_tf_fields_y(const DevOptics* opt, const Sampling& sm, int npat
   const int thr = threads_for((long)sm.ny * nf * W);
   const size_t lds = (size_t)(sm.ny + sm.ny * nf * W) * sizeof(float2);
   ScopedTiming _t("k_tf_fields_y", s);
+#define WO_FIELDS(NN, FF, AA)                                                                    \
+  hipLaunchKernelGGL((k_tf_fields_y<NN, FF, AA>), dim3((unsigned)nwg), dim3(thr), lds, s, opt, sm, ab, \
+                     partials, W, tiles, ZC, plan)
 #define X_(NN)                                                                                   \
   case NN:                                                                                       \
-    if (nf == 2)                                                                                 \
-      hipLaunchKernelGGL((k_tf_fields_y<NN, 2>), dim3((unsigned)nwg), dim3(thr), lds, s, opt, \
-                         sm, ab, partials, W, tiles, ZC, plan);                                  \
-    else                                                                                         \
-      hipLaunchKernelGGL((k_tf_fields_y<NN, 1>), dim3((unsigned)nwg), dim3(thr), lds, s, opt, sm, \
-                         ab, partials, W, tiles, ZC, plan);                                      \
+    if (nf == 2) {                                                                               \
+      if (sm.aberrated) WO_FIELDS(NN, 2, true); else WO_FIELDS(NN, 2, false);                    \
+    } else {                                                                                     \
+      if (sm.aberrated) WO_FIELDS(NN, 1, true); else WO_FIELDS(NN, 1, false);                    \
+    }                                                                                            \
     return hipGetLastError();
   switch (sm.ny) {
     WO_LATERAL_SIZES(X_)
@@ -366,12 +371,12 @@ hipError_t launch_tf_fields_y(const DevOptics* opt, const Sampling& sm, int npat
       break;
   }
 #undef X_
-  if (nf == 2)
-    hipLaunchKernelGGL((k_tf_fields_y<0, 2>), dim3((unsigned)nwg), dim3(thr), lds, s, opt, sm, ab,
-                       partials, W, tiles, ZC, plan);
-  else
-    hipLaunchKernelGGL((k_tf_fields_y<0, 1>), dim3((unsigned)nwg), dim3(thr), lds, s, opt, sm, ab,
-                       partials, W, tiles, ZC, plan);
+  if (nf == 2) {
+    if (sm.aberrated) WO_FIELDS(0, 2, true); else WO_FIELDS(0, 2, false);
+  } else {
+    if (sm.aberrated) WO_FIELDS(0, 1, true); else WO_FIELDS(0, 1, false);
+  }
+#undef WO_FIELDS
   return hipGetLastError();
 }
 
