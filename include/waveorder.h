@@ -168,9 +168,11 @@ int wo_adjoint(const wo_optics* o, int32_t n, const void* tf, const float* r, fl
  * Tikhonov phase reconstruction.  Gradients are hand-written reverse mode
  * through the solve and the transfer-function synthesis; the transfer
  * function is recomputed every iteration.  Soft pupil edges (edge_width > 0)
- * are needed for non-zero NA and tilt gradients.  Aberrated optics (any
- * zernike coefficient non-zero) are not accepted here (WO_EUNSUPPORTED): the
- * gradient has no aberration terms. */
+ * are needed for non-zero NA and tilt gradients.  Aberrated optics are
+ * accepted (their aberration stays fixed while theta moves; dL/dNA includes
+ * the NA dependence of the aberration through rho); the gradient with respect
+ * to the aberration coefficients themselves comes from
+ * wo_midband_loss_grad_aberration. */
 
 /* Unlike the calls above, the calls of this section accept patches of uneven
  * shapes (each o[i] its own nz >= 2, ny and nx <= 2048, dz, dy, dx): the stacks are
@@ -190,6 +192,16 @@ size_t wo_tune_workspace_size(const wo_optics* o, int32_t n, int32_t starts);
 int wo_midband_loss_grad(const wo_optics* o, int32_t n, const float* d, const double* eta,
                          const double* nu_c, double* loss_out, double* grad_out, void* ws,
                          size_t ws_bytes, void* stream);
+
+/* As wo_midband_loss_grad, with grad_out host [n][11]: dL/d(defocus, na_det,
+ * tilt_zenith, tilt_azimuth) then dL/d zernike[0..6] (Noll 5..11, per wave).
+ * The aberration phase 2 pi W multiplies both arms of the transfer function,
+ * so dA/dc_j = i 2 pi Z_j A and dB/dc_j = i 2 pi Z_j B (Table 1 with the
+ * aberrated detection pupil); the terms are summed with the same reverse-mode
+ * factors as the defocus gradient.  Valid at zero coefficients too. */
+int wo_midband_loss_grad_aberration(const wo_optics* o, int32_t n, const float* d, const double* eta,
+                                    const double* nu_c, double* loss_out, double* grad_out, void* ws,
+                                    size_t ws_bytes, void* stream);
 
 typedef struct wo_autotune_opts {
   int32_t iters;           /* Adam iterations (the paper uses 100) */

@@ -78,6 +78,23 @@ def fd_gradient(o: op.Optics, d, eta, nu_c, steps, which=(0, 1, 2, 3)) -> np.nda
     return g
 
 
+def fd_gradient_aberration(o: op.Optics, d, eta, nu_c, h=1e-3, n=7) -> np.ndarray:
+    """dL/d zernike[j] (j < n, per wave) by central differences with one Richardson
+    step (h and h/2), the other coefficients and theta held (R18)."""
+    c0 = np.zeros(n)
+    c0[: len(o.zernike)] = o.zernike[:n]
+    g = np.zeros(n)
+    for j in range(n):
+        def cd(step):
+            cp, cm = c0.copy(), c0.copy()
+            cp[j] += step
+            cm[j] -= step
+            return (loss(o.replace(zernike=tuple(cp)), d, eta, nu_c)
+                    - loss(o.replace(zernike=tuple(cm)), d, eta, nu_c)) / (2 * step)
+        g[j] = (4.0 * cd(h / 2) - cd(h)) / 3.0
+    return g
+
+
 # --- analytic reverse-mode gradient (Ext. Data Fig. 3, dashed arrows)
 
 def _edge_slope(inside: np.ndarray, halfwidth: float) -> np.ndarray:

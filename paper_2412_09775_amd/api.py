@@ -38,7 +38,7 @@ SYMBOLS = ("wo_bank_shape", "wo_workspace_size", "wo_transfer_function", "wo_for
            "wo_cnn_train_step", "wo_conv3d_forward", "wo_conv3d_input_grad", "wo_conv3d_weight_grad",
            "wo_synth_thin_cells", "wo_add_gaussian_noise", "wo_crop_stacks", "wo_fft_tune",
            "wo_fft_plans_export", "wo_fft_plans_import", "wo_fft_plans_clear", "wo_fft_candidates",
-           "wo_tile_grid", "wo_stitch_tiles", "wo_timing_select")
+           "wo_tile_grid", "wo_stitch_tiles", "wo_timing_select", "wo_midband_loss_grad_aberration")
 
 _FIELDS = ("model", "nz", "ny", "nx", "dz", "dy", "dx", "wavelength", "na_ill", "na_det",
            "n_medium", "defocus", "tilt_zenith", "tilt_azimuth", "edge_width", "swing")
@@ -120,6 +120,7 @@ def load(path: str = LIB_PATH):
     lib.wo_tune_workspace_size.argtypes = [op, i32, i32]
     lib.wo_tune_workspace_size.restype = sz
     lib.wo_midband_loss_grad.argtypes = [op, i32, vp, dp, dp, dp, dp, vp, sz, vp]
+    lib.wo_midband_loss_grad_aberration.argtypes = [op, i32, vp, dp, dp, dp, dp, vp, sz, vp]
     lib.wo_autotune.argtypes = [op, i32, vp, dp, ctypes.POINTER(WoAutotuneOpts), dp, vp, sz, vp]
     lib.wo_restore_tiles.argtypes = [op, i32, vp, dp, ctypes.POINTER(WoAutotuneOpts), dp, vp, vp, sz,
                                      vp]
@@ -336,9 +337,10 @@ def pack_stacks(stacks):
     return stacks.contiguous()
 
 
-def midband_loss_grad(optics, d, eta, nu_c=None, ws=None, stream=None):
+def midband_loss_grad(optics, d, eta, nu_c=None, ws=None, stream=None, aberration=False):
     """Mid-band loss and dL/dtheta per patch (numpy arrays (n,), (n, 4)); `d` as in
-    pack_stacks (patches may differ in shape)."""
+    pack_stacks (patches may differ in shape).  aberration=True: (n, 11), theta then
+    the seven Zernike coefficients (wo_midband_loss_grad_aberration)."""
     import numpy as np
     import torch
     lib = load()
@@ -351,11 +353,11 @@ def midband_loss_grad(optics, d, eta, nu_c=None, ws=None, stream=None):
     eta_a, eta_p = _dbl(np.broadcast_to(eta, (n,)))
     nu_a, nu_p = _dbl(np.zeros(n) if nu_c is None else np.broadcast_to(nu_c, (n,)))
     loss = np.zeros(n)
-    grad = np.zeros((n, 4))
-    _check(lib.wo_midband_loss_grad(arr, n, _ptr(d), eta_p, nu_p,
-                                    loss.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
-                                    grad.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
-                                    _ptr(ws), ws.numel(), _stream(stream)), "wo_midband_loss_grad")
+    grad = np.zeros((n, 4 + N_ZERNIKE if aberration else 4))
+    fn = lib.wo_midband_loss_grad_aberration if aberration else lib.wo_midband_loss_grad
+    _check(fn(arr, n, _ptr(d), eta_p, nu_p, loss.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+              grad.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), _ptr(ws), ws.numel(),
+              _stream(stream)), "wo_midband_loss_grad")
     return loss, grad
 
 

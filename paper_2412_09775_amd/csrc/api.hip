@@ -357,7 +357,7 @@ TuneLayout tune_layout(const wo_optics* o, int32_t n, int32_t starts) {
   L.off_lp = take((size_t)L.nv * L.lbpp * sizeof(double));
   L.off_dp = take((size_t)L.nv * L.dwpp * sizeof(double));
   const long gt = grad_tiles(sm);
-  L.off_gp = take((size_t)L.nv * Z * gt * 4 * sizeof(double));
+  L.off_gp = take((size_t)L.nv * Z * gt * kGradAll * sizeof(double));
   L.off_ip = take((size_t)L.nv * gt * 4 * sizeof(double));
   L.off_ropt = take((size_t)n * sizeof(DevOptics));
   L.off_reta = take((size_t)n * sizeof(float));
@@ -374,6 +374,7 @@ struct TuneGroup {
   TuneLayout L;
   size_t base;
   double work;
+  int ab = 0;            // aberration-aware kernels (an aberrated patch, or dL/dc wanted)
 };
 
 std::vector<TuneGroup> tune_groups(const wo_optics* o, int32_t n, int32_t starts, size_t* total) {
@@ -383,6 +384,7 @@ std::vector<TuneGroup> tune_groups(const wo_optics* o, int32_t n, int32_t starts
     while (k < g.size() && !same_sampling(g[k].rep, &o[i])) ++k;
     if (k == g.size()) g.push_back(TuneGroup{&o[i], {}, TuneLayout{}, 0, 0.0});
     g[k].idx.push_back(i);
+    if (aberrated(o[i])) g[k].ab = 1;
   }
   size_t b = 0;
   for (auto& t : g) {
@@ -460,7 +462,8 @@ DevOptics dev_optics(const wo_optics& o) {
 int tune_iteration(const TuneGroup& g, char* ws, int starts, int update, hipStream_t hs) {
   const TuneLayout& L = g.L;
   char* w = ws + g.base;
-  const Sampling sm = sampling_of(g.rep);
+  Sampling sm = sampling_of(g.rep);
+  sm.aberrated = g.ab;
   const long Z = sm.nz, Y = sm.ny, Xh = sm.nx / 2 + 1;
   const long plane = Y * Xh;
   DevOptics* dopt = (DevOptics*)(w + L.off_opt);
@@ -493,7 +496,8 @@ int tune_restore(const TuneGroup& g, char* ws, int starts, float* f_out, const s
                  hipStream_t hs) {
   const TuneLayout& L = g.L;
   char* w = ws + g.base;
-  const Sampling sm = sampling_of(g.rep);
+  Sampling sm = sampling_of(g.rep);
+  sm.aberrated = g.ab;
   const long Z = sm.nz, Y = sm.ny, X = sm.nx, Xh = X / 2 + 1;
   const long plane = Y * Xh;
   const int np = L.np;
@@ -527,7 +531,6 @@ int validate_thin(const wo_optics* o, int32_t n) {
     if (st) return st;
     if (o[i].model != WO_MODEL_LABELFREE_THIN || o[i].nz < 2 || o[i].ny > 2048 || o[i].nx > 2048)
       return WO_EUNSUPPORTED;
-    if (aberrated(o[i])) return WO_EUNSUPPORTED;   // the gradient has no aberration terms
     st = check_optics(&o[i]);
     if (st) return st;
   }
@@ -1061,9 +1064,9 @@ size_t wo_tune_workspace_size(const wo_optics* o, int32_t n, int32_t starts) {
   return total;
 }
 
-int wo_midband_loss_grad(const wo_optics* o, int32_t n, const float* d, const double* eta,
-                         const double* nu_c, double* loss_out, double* grad_out, void* ws,
-                         size_t ws_bytes, void* stream) {
+static int midband(const wo_optics* o, int32_t n, const float* d, const double* eta, const double* nu_c,
+                   double* loss_out, double* grad_out, int with_aberration, void* ws, size_t ws_bytes,
+                   void* stream) {
   int st = validate_thin(o, n);
   if (st) return st;
   if (!d || !eta || !ws || !loss_out) return WO_EINVAL;
@@ -1072,6 +1075,8 @@ int wo_midband_loss_grad(const wo_optics* o, int32_t n, const float* d, const do
   size_t need = 0;
   std::vector<TuneGroup> groups = tune_groups(o, n, 1, &need);
   if (ws_bytes < need) return WO_ENOMEM;
+  if (with_aberration)
+    for (auto& g : groups) g.ab = 1;
   const std::vector<size_t> doff = packed_offsets(o, n, true);
   hipStream_t hs = (hipStream_t)stream;
   char* w = (char*)ws;
@@ -1089,11 +1094,27 @@ int wo_midband_loss_grad(const wo_optics* o, int32_t n, const float* d, const do
     for (int j = 0; j < g.L.np; ++j) {
       const int i = g.idx[j];
       loss_out[i] = h[j].loss;
-      if (grad_out)
+      if (grad_out && with_aberration) {
+        for (int k = 0; k < 4; ++k) grad_out[kGradAll * i + k] = h[j].grad[k];
+        for (int k = 0; k < 7; ++k) grad_out[kGradAll * i + 4 + k] = h[j].gab[k];
+      } else if (grad_out) {
         for (int k = 0; k < 4; ++k) grad_out[4 * i + k] = h[j].grad[k];
+      }
     }
   }
   return WO_OK;
+}
+
+int wo_midband_loss_grad(const wo_optics* o, int32_t n, const float* d, const double* eta,
+                         const double* nu_c, double* loss_out, double* grad_out, void* ws,
+                         size_t ws_bytes, void* stream) {
+  return midband(o, n, d, eta, nu_c, loss_out, grad_out, 0, ws, ws_bytes, stream);
+}
+
+int wo_midband_loss_grad_aberration(const wo_optics* o, int32_t n, const float* d, const double* eta,
+                                    const double* nu_c, double* loss_out, double* grad_out, void* ws,
+                                    size_t ws_bytes, void* stream) {
+  return midband(o, n, d, eta, nu_c, loss_out, grad_out, 1, ws, ws_bytes, stream);
 }
 
 int wo_autotune(wo_optics* o, int32_t n, const float* d, const double* eta,

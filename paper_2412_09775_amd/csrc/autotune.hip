@@ -267,7 +267,7 @@ hipError_t launch_tf_rows_bwd(const double* partials, const Sampling& sm, int nv
 // tile and a chunk of ZC planes; the pupils and their derivatives, which do not
 // depend on z, are evaluated once.  gpart[((v*nzc + chunk)*tiles + tile)*4 + j];
 // the first chunk also writes dI_bg/dtheta partials to ipart[(v*tiles + tile)*4 + j].
-template <int NS>
+template <int NS, bool AB>
 __global__ __launch_bounds__(1024) void k_tf_grad_y(const DevOptics* __restrict__ opt, Sampling sm,
                                                     const float2* __restrict__ ab,
                                                     double* __restrict__ gpart,
@@ -294,6 +294,11 @@ __global__ __launch_bounds__(1024) void k_tf_grad_y(const DevOptics* __restrict_
   // products of the contraction (FP32)
   double tkz[EPT];
   float SP[EPT], gkP[EPT], SdP[EPT], gkdP[EPT], dSzP[EPT], dSaP[EPT];
+  // aberration-aware (AB): the aberration phase 2 W in units of pi, and
+  // Q = sum_z (S P Im(U_A e) + gk P Re(U_B e)), which every derivative of the
+  // aberration phase multiplies (d/dc_j: -2 pi Z_j; the NA term: -2 pi dW/dNA)
+  float ab2[AB ? EPT : 1];
+  double Qe[AB ? EPT : 1];
   {
     const double hw = soft_halfwidth(o, sm);
     const double km = o.n_medium / o.wavelength;
@@ -308,6 +313,10 @@ __global__ __launch_bounds__(1024) void k_tf_grad_y(const DevOptics* __restrict_
     for (int i = 0; i < EPT; ++i) {
       tkz[i] = 0.0;
       SP[i] = gkP[i] = SdP[i] = gkdP[i] = dSzP[i] = dSaP[i] = 0.f;
+      if constexpr (AB) {
+        ab2[i] = 0.f;
+        Qe[i] = 0.0;
+      }
       const int e = tid + i * nthr;
       if (e >= Y * W) continue;
       const int ky = e >> wsh, w = e & (W - 1);
@@ -332,6 +341,7 @@ __global__ __launch_bounds__(1024) void k_tf_grad_y(const DevOptics* __restrict_
       const double kz = sqrt(fmax(km * km - rp * rp, 0.0));
       const double gk = kz > 0.0 ? km / kz : 0.0;
       tkz[i] = 2.0 * kz;
+      if constexpr (AB) ab2[i] = (float)(2.0 * aberration_waves(o, fy, fx));
       // A = S P e, B = P (i km / kz) e with e = e^{i 2 pi kz (z - dz0)}
       SP[i] = (float)(S * P);
       gkP[i] = (float)(gk * P);
@@ -386,7 +396,8 @@ __global__ __launch_bounds__(1024) void k_tf_grad_y(const DevOptics* __restrict_
                          dSzP[i] == 0.f && dSaP[i] == 0.f))
         continue;
       const int ky = e >> wsh, w = e & (W - 1);
-      const double arg = tkz[i] * dzr;
+      double arg = tkz[i] * dzr;
+      if constexpr (AB) arg += (double)ab2[i];
       const float red_arg = (float)(arg - 2.0 * rint(0.5 * arg));
       float snf, csf;
       sincospif(red_arg, &snf, &csf);
@@ -398,7 +409,9 @@ __global__ __launch_bounds__(1024) void k_tf_grad_y(const DevOptics* __restrict_
       const float tpk = (float)(M_PI * tkz[i]);                                       // 2 pi kz
       // d/d defocus multiplies A and B by -i 2 pi kz:
       //   Re(U_A A (-i tpk)) = tpk S P Im(U_A e); Re(U_B B (-i tpk)) = tpk gk P Re(U_B e)
-      g[0] += (double)(tpk * (SP[i] * ua_im + gkP[i] * ub_re));
+      const float qv = SP[i] * ua_im + gkP[i] * ub_re;
+      g[0] += (double)(tpk * qv);
+      if constexpr (AB) Qe[i] += (double)qv;
       // d/dNA: A' = S dP e, B' = dP i gk e -> Re(U_B e i gk dP) = -gk dP Im(U_B e)
       g[1] += (double)(SdP[i] * ua_re - gkdP[i] * ub_im);
       g[2] += (double)(dSzP[i] * ua_re);
@@ -406,10 +419,26 @@ __global__ __launch_bounds__(1024) void k_tf_grad_y(const DevOptics* __restrict_
     }
     __syncthreads();
   }
+  constexpr int KG = AB ? kGradAll : 4;
+  double ga[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  if constexpr (AB) {
+    const double tp = 2.0 * M_PI;
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    const double t = block_sum_d(4.0 * g[j], red);
-    if (tid == 0) gpart[((v * nzc + zc) * tiles_x + tile) * 4 + j] = t;
+    for (int i = 0; i < EPT; ++i) {
+      const int e = tid + i * nthr;
+      if (e >= Y * W || Qe[i] == 0.0) continue;
+      const int ky = e >> wsh, kx = x0 + (e & (W - 1));
+      double zj[7], dwdna;
+      zernike_terms(o, fftfreq(ky, Y, sm.dy), fftfreq(kx, X, sm.dx), zj, &dwdna);
+      g[1] -= tp * dwdna * Qe[i];
+#pragma unroll
+      for (int j = 0; j < 7; ++j) ga[j] -= tp * zj[j] * Qe[i];
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < KG; ++j) {
+    const double t = block_sum_d(4.0 * (j < 4 ? g[j] : ga[j - 4]), red);
+    if (tid == 0) gpart[((v * nzc + zc) * tiles_x + tile) * KG + j] = t;
   }
 }
 
@@ -452,10 +481,12 @@ hipError_t launch_tf_grad_y(const DevOptics* opt, const Sampling& sm, int nv, co
   const int thr = grad_threads(sm);
   const size_t lds = (size_t)(sm.ny + sm.ny * 2 * W) * sizeof(float2);
   ScopedTiming _t("k_tf_grad_y", s);
+#define WO_GRAD(NN, AA)                                                                          \
+  hipLaunchKernelGGL((k_tf_grad_y<NN, AA>), dim3((unsigned)nwg), dim3(thr), lds, s, opt, sm, ab, gpart, \
+                     ipart, W, tiles, ZC, plan)
 #define X_(NN)                                                                                   \
   case NN:                                                                                       \
-    hipLaunchKernelGGL((k_tf_grad_y<NN>), dim3((unsigned)nwg), dim3(thr), lds, s, opt, sm, ab, gpart, \
-                       ipart, W, tiles, ZC, plan);                                               \
+    if (sm.aberrated) WO_GRAD(NN, true); else WO_GRAD(NN, false);                                \
     return hipGetLastError();
   switch (sm.ny) {
     WO_LATERAL_SIZES(X_)
@@ -463,8 +494,8 @@ hipError_t launch_tf_grad_y(const DevOptics* opt, const Sampling& sm, int nv, co
       break;
   }
 #undef X_
-  hipLaunchKernelGGL((k_tf_grad_y<0>), dim3((unsigned)nwg), dim3(thr), lds, s, opt, sm, ab, gpart, ipart,
-                     W, tiles, ZC, plan);
+  if (sm.aberrated) WO_GRAD(0, true); else WO_GRAD(0, false);
+#undef WO_GRAD
   return hipGetLastError();
 }
 
@@ -493,11 +524,14 @@ __global__ __launch_bounds__(256) void k_adam(DevOptics* __restrict__ opt,
   acc = 0.0;
   for (long i = tid; i < tiles_x; i += blockDim.x) acc += ppart[v * tiles_x + i];
   const double ibg = block_sum_d(acc, red);
-  double gj[4], dij[4];
-  for (int j = 0; j < 4; ++j) {
+  const int KG = sm.aberrated ? kGradAll : 4;
+  double gj[kGradAll], dij[4];
+  for (int j = 0; j < KG; ++j) {
     acc = 0.0;
-    for (long i = tid; i < gn; i += blockDim.x) acc += gpart[(v * gn + i) * 4 + j];
+    for (long i = tid; i < gn; i += blockDim.x) acc += gpart[(v * gn + i) * KG + j];
     gj[j] = block_sum_d(acc, red);
+  }
+  for (int j = 0; j < 4; ++j) {
     acc = 0.0;
     for (long i = tid; i < gtiles; i += blockDim.x) acc += ipart[(v * gtiles + i) * 4 + j];
     dij[j] = block_sum_d(acc, red);
@@ -510,6 +544,8 @@ __global__ __launch_bounds__(256) void k_adam(DevOptics* __restrict__ opt,
   for (int j = 0; j < 4; ++j) grad[j] = gj[j] - 4.0 * dsum / (N * ibg * ibg) * dij[j];
   s.loss = loss;
   for (int j = 0; j < 4; ++j) s.grad[j] = grad[j];
+  // I_bg = sum S |P|^2 does not depend on the aberration
+  for (int j = 0; j < 7; ++j) s.gab[j] = KG > 4 ? gj[4 + j] : 0.0;
   if (update) {
     DevOptics o = opt[v];
     double th[4] = {o.defocus, o.na_det, o.tilt_zenith, o.tilt_azimuth};

@@ -454,6 +454,32 @@ __host__ __device__ inline double aberration_waves(const DevOptics& o, double fy
          o.zern[6] * k5 * (6.0 * r2 * r2 - 6.0 * r2 + 1.0);
 }
 
+// The seven polynomials Z_5..Z_11 at p (zj) and dW/dNA_det of the aberration
+// (W depends on NA_det through rho = |p| lambda0 / NA_det: dW/dNA = -(rho /
+// NA) sum_j c_j dZ_j/drho).
+__host__ __device__ inline void zernike_terms(const DevOptics& o, double fy, double fx, double zj[7],
+                                              double* dw_dna) {
+  const double pr = sqrt(fy * fy + fx * fx);
+  const double r = pr / (o.na_det / o.wavelength), r2 = r * r, r3 = r2 * r;
+  const double s1 = pr > 0.0 ? fy / pr : 0.0, c1 = pr > 0.0 ? fx / pr : 1.0;
+  const double s2 = 2.0 * s1 * c1, c2 = c1 * c1 - s1 * s1;
+  const double s3 = s2 * c1 + c2 * s1, c3 = c2 * c1 - s2 * s1;
+  const double k6 = 2.449489742783178, k8 = 2.8284271247461903, k5 = 2.23606797749979;
+  zj[0] = k6 * r2 * s2;
+  zj[1] = k6 * r2 * c2;
+  zj[2] = k8 * (3.0 * r3 - 2.0 * r) * s1;
+  zj[3] = k8 * (3.0 * r3 - 2.0 * r) * c1;
+  zj[4] = k8 * r3 * s3;
+  zj[5] = k8 * r3 * c3;
+  zj[6] = k5 * (6.0 * r2 * r2 - 6.0 * r2 + 1.0);
+  const double d[7] = {2.0 * k6 * r * s2, 2.0 * k6 * r * c2, k8 * (9.0 * r2 - 2.0) * s1,
+                       k8 * (9.0 * r2 - 2.0) * c1, 3.0 * k8 * r2 * s3, 3.0 * k8 * r2 * c3,
+                       k5 * (24.0 * r3 - 12.0 * r)};
+  double dw = 0.0;
+  for (int j = 0; j < 7; ++j) dw += o.zern[j] * d[j];
+  *dw_dna = -(r / o.na_det) * dw;
+}
+
 // Azimuthal sector k of the direction (dy, dx): the azimuth, from +x towards +y,
 // lies in [k pi/4, (k+1) pi/4); the origin is in sector 0.  Comparisons only.
 __host__ __device__ __forceinline__ int octant(double dy, double dx) {
@@ -471,9 +497,14 @@ struct TuneState {
   double lr[4], lo[4], hi[4];
   double eta, nu_c, band_count;
   double loss, grad[4];
+  double gab[7];   // dL / d zernike[j] (filled when the gradient is aberration-aware)
   int t, mask;
   int pad[2];
 };
+
+// Gradient components per partial: theta (4), then the 7 aberration coefficients
+// when the gradient kernels run aberration-aware.
+constexpr int kGradAll = 11;
 
 // Sampling shared by every patch of a call.
 struct Sampling {
