@@ -225,11 +225,16 @@ typedef struct wo_autotune_opts {
   int32_t branches;        /* graph modes: concurrent branches the shape groups
                               are spread over (0: 4; at most 8), balanced by
                               voxels x starts */
+  double lr_zernike;       /* Adam rate of the aberration coefficients: tune_mask
+                              bit 4 + j tunes zernike[j] (Noll 5 + j), starting from
+                              each patch's optics (also for every multistart start) */
+  double zernike_bound;    /* box [-bound, bound] waves for them (<= 0: 1 wave) */
 } wo_autotune_opts;
 
 /* Adam (beta 0.9, 0.999, eps 1e-8) on theta for opts->iters iterations, every
  * patch and start in one batched launch sequence; theta is clipped to the box
- * after each step.  On return o[i] holds the best start's theta and
+ * after each step.  On return o[i] holds the best start's theta (and tuned
+ * aberration coefficients) and
  * loss_out[i] (host, may be NULL) its loss at that theta.  d: device, packed
  * stacks; eta: host [n].  Not reentrant across host threads (calls
  * serialise on a library lock).  Synchronises `stream` before returning. */

@@ -222,3 +222,17 @@ def autotune(o: op.Optics, d, eta, nu_c, iters, lr, lo, hi, mask=(1, 1, 1, 0)):
         _, g = loss_and_gradient(with_theta(o, st.theta), d, eta, nu_c)
         adam_step(st, g, lr, lo, hi, mask=msk)
     return st.theta, loss(with_theta(o, st.theta), d, eta, nu_c)
+
+
+def autotune_aberration(o: op.Optics, d, eta, nu_c, iters, lr, bound, mask=(1,) * 7):
+    """Adam on the seven Zernike coefficients (theta held) for ``iters`` iterations from
+    o's coefficients, gradients by central differences of the loss, box [-bound,
+    bound]; returns (coefficients, loss)."""
+    c0 = np.zeros(7)
+    c0[: len(o.zernike)] = o.zernike[:7]
+    st = AdamState(c0.copy(), np.zeros(7), np.zeros(7))
+    msk = np.asarray(mask, dtype=np.float64)
+    for _ in range(iters):
+        g = fd_gradient_aberration(o.replace(zernike=tuple(st.theta)), d, eta, nu_c)
+        adam_step(st, g, lr, -bound, bound, mask=msk)
+    return st.theta, loss(o.replace(zernike=tuple(st.theta)), d, eta, nu_c)

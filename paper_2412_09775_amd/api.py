@@ -82,7 +82,8 @@ class WoAutotuneOpts(ctypes.Structure):
                 ("lr", ctypes.c_double * 4), ("lo", ctypes.c_double * 4), ("hi", ctypes.c_double * 4),
                 ("theta0", ctypes.POINTER(ctypes.c_double)), ("nu_c", ctypes.POINTER(ctypes.c_double)),
                 ("all_theta_out", ctypes.POINTER(ctypes.c_double)),
-                ("all_loss_out", ctypes.POINTER(ctypes.c_double)), ("branches", ctypes.c_int32)]
+                ("all_loss_out", ctypes.POINTER(ctypes.c_double)), ("branches", ctypes.c_int32),
+                ("lr_zernike", ctypes.c_double), ("zernike_bound", ctypes.c_double)]
 
 
 class WoError(RuntimeError):
@@ -362,7 +363,7 @@ def midband_loss_grad(optics, d, eta, nu_c=None, ws=None, stream=None, aberratio
 
 
 def _tune_call(fn, name, optics, d, eta, iters, lr, lo, hi, mask, multistart, theta0, nu_c, use_graph,
-               branches, ws, stream, extra):
+               branches, ws, stream, extra, lr_zernike=0.0, zernike_bound=0.0):
     import copy
     import numpy as np
     import torch
@@ -377,6 +378,7 @@ def _tune_call(fn, name, optics, d, eta, iters, lr, lo, hi, mask, multistart, th
     opts = WoAutotuneOpts()
     opts.iters, opts.multistart, opts.use_graph, opts.tune_mask = int(iters), M, int(use_graph), int(mask)
     opts.branches = int(branches)
+    opts.lr_zernike, opts.zernike_bound = float(lr_zernike), float(zernike_bound)
     for j in range(4):
         opts.lr[j], opts.lo[j], opts.hi[j] = float(lr[j]), float(lo[j]), float(hi[j])
     keep = []
@@ -405,17 +407,25 @@ def _tune_call(fn, name, optics, d, eta, iters, lr, lo, hi, mask, multistart, th
                 oo[f] = getattr(arr[i], f)
             else:
                 setattr(oo, f, getattr(arr[i], f))
+        if (int(mask) >> 4) & 0x7F:
+            z = tuple(float(arr[i].zernike[j]) for j in range(N_ZERNIKE))
+            if isinstance(oo, dict):
+                oo["zernike"] = z
+            else:
+                oo.zernike = z
         out.append(oo)
     return out, loss, all_theta, all_loss
 
 
 def autotune(optics, d, eta, iters=100, lr=PAPER_LR, lo=(-1e300,) * 4, hi=(1e300,) * 4,
              mask=0b0111, multistart=1, theta0=None, nu_c=None, use_graph=False, branches=0, ws=None,
-             stream=None):
+             stream=None, lr_zernike=0.0, zernike_bound=0.0):
     """Adam auto-tune of theta for every patch; returns (optics list, loss, all_theta, all_loss).
-    `d` as in pack_stacks; use_graph 0/False, 1/True (one iteration replayed) or 2 (one launch)."""
+    `d` as in pack_stacks; use_graph 0/False, 1/True (one iteration replayed) or 2 (one launch).
+    mask bits 4..10 also tune the Zernike coefficients (rate lr_zernike, box +-zernike_bound)."""
     return _tune_call(load().wo_autotune, "wo_autotune", optics, d, eta, iters, lr, lo, hi, mask,
-                      multistart, theta0, nu_c, use_graph, branches, ws, stream, ())
+                      multistart, theta0, nu_c, use_graph, branches, ws, stream, (),
+                      lr_zernike, zernike_bound)
 
 
 def restore_tiles(optics, d, eta, iters=20, lr=PAPER_LR, lo=(-1e300,) * 4, hi=(1e300,) * 4,

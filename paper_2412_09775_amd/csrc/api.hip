@@ -553,7 +553,7 @@ void clamp_box(const wo_optics* o, double lo[4], double hi[4]) {
 int tune_setup(const wo_optics* o, const TuneGroup& g, int starts, const double* theta0,
                const float* d, const size_t* doff, const double* eta, const double* nu_c,
                const double* lr, const double* lo, const double* hi, int mask, char* ws,
-               hipStream_t hs) {
+               hipStream_t hs, double lr_ab = 0.0, double bound_ab = 0.0) {
   const TuneLayout& L = g.L;
   char* w = ws + g.base;
   const int np = L.np, nv = L.nv;
@@ -587,6 +587,8 @@ int tune_setup(const wo_optics* o, const TuneGroup& g, int starts, const double*
         t.lo[k] = blo[k];
         t.hi[k] = bhi[k];
       }
+      t.lr_ab = lr_ab;
+      t.bound_ab = bound_ab > 0.0 ? bound_ab : 1.0;
       t.eta = eta[i];
       t.nu_c = nuc;
       t.band_count = bc;
@@ -669,7 +671,9 @@ std::string graph_key(const wo_optics* o, int32_t n, const wo_autotune_opts* opt
            B, ws, ws_bytes, (const void*)d, (const void*)f_out, fft_table_version());
   k += b;
   for (int i = 0; i < n; ++i) {
-    snprintf(b, sizeof(b), "%d %d %d %a %a %a;", o[i].nz, o[i].ny, o[i].nx, o[i].dz, o[i].dy, o[i].dx);
+    // the aberration-aware kernel variants are part of the graph
+    snprintf(b, sizeof(b), "%d %d %d %a %a %a %d;", o[i].nz, o[i].ny, o[i].nx, o[i].dz, o[i].dy, o[i].dx,
+             aberrated(o[i]) || ((opts->tune_mask >> 4) & 0x7f) ? 1 : 0);
     k += b;
   }
   return k;
@@ -707,9 +711,15 @@ int run_tune(wo_optics* o, int32_t n, const float* d, const double* eta,
   if (opts->branches < 0 || opts->branches > kMaxBranches) return WO_EINVAL;
   for (int i = 0; i < n; ++i)
     if (!(eta[i] > 0.0)) return WO_EINVAL;
+  if ((opts->tune_mask >> 4) & 0x7f) {
+    if (!(opts->lr_zernike >= 0.0) || !isfinite(opts->lr_zernike) || !isfinite(opts->zernike_bound))
+      return WO_EINVAL;
+  }
   size_t need = 0;
   std::vector<TuneGroup> groups = tune_groups(o, n, starts, &need);
   if (ws_bytes < need) return WO_ENOMEM;
+  if ((opts->tune_mask >> 4) & 0x7f)
+    for (auto& g : groups) g.ab = 1;   // tuned coefficients need the aberration-aware kernels
   const std::vector<size_t> doff = packed_offsets(o, n, true);
   const std::vector<size_t> foff = packed_offsets(o, n, false);
   hipStream_t hs = (hipStream_t)stream;
@@ -717,7 +727,7 @@ int run_tune(wo_optics* o, int32_t n, const float* d, const double* eta,
   std::lock_guard<std::mutex> lk(g_tune_mu);
   for (auto& g : groups) {
     st = tune_setup(o, g, starts, opts->theta0, d, doff.data(), eta, opts->nu_c, opts->lr, opts->lo,
-                    opts->hi, opts->tune_mask, w, hs);
+                    opts->hi, opts->tune_mask, w, hs, opts->lr_zernike, opts->zernike_bound);
     if (st) return st;
   }
   const int iters = opts->iters;
@@ -829,6 +839,8 @@ int run_tune(wo_optics* o, int32_t n, const float* d, const double* eta,
       o[i].na_det = ho[best].na_det;
       o[i].tilt_zenith = ho[best].tilt_zenith;
       o[i].tilt_azimuth = ho[best].tilt_azimuth;
+      if ((opts->tune_mask >> 4) & 0x7f)
+        for (int k = 0; k < 7; ++k) o[i].zernike[k] = ho[best].zern[k];
       if (loss_out) loss_out[i] = h[best].loss;
       if (opts->all_theta_out)
         for (int s2 = 0; s2 < starts; ++s2) {

@@ -565,6 +565,16 @@ __global__ __launch_bounds__(256) void k_adam(DevOptics* __restrict__ opt,
     opt[v].na_det = th[1];
     opt[v].tilt_zenith = th[2];
     opt[v].tilt_azimuth = th[3];
+    for (int j = 0; j < 7; ++j) {
+      if (!((s.mask >> (4 + j)) & 1)) continue;
+      const double gm = s.gab[j];
+      s.mab[j] = b1 * s.mab[j] + (1.0 - b1) * gm;
+      s.vab[j] = b2 * s.vab[j] + (1.0 - b2) * gm * gm;
+      const double mh = s.mab[j] / c1, vh = s.vab[j] / c2;
+      double t = (double)o.zern[j] - s.lr_ab * mh / (sqrt(vh) + eps);
+      t = t < -s.bound_ab ? -s.bound_ab : (t > s.bound_ab ? s.bound_ab : t);
+      opt[v].zern[j] = (float)t;
+    }
   }
   st[v] = s;
 }

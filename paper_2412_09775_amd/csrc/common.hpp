@@ -498,6 +498,9 @@ struct TuneState {
   double eta, nu_c, band_count;
   double loss, grad[4];
   double gab[7];   // dL / d zernike[j] (filled when the gradient is aberration-aware)
+  // Adam on the aberration coefficients (mask bits 4..10): moments, one rate
+  // and the box [-bound, bound] shared by the seven
+  double mab[7], vab[7], lr_ab, bound_ab;
   int t, mask;
   int pad[2];
 };

@@ -229,3 +229,23 @@ def test_aberration_gradient_matches_finite_differences(gpu_lib, problem, coeffs
     _, g4 = gpu_lib.midband_loss_grad([o], dd, etas[:1], nu_c)
     if any(coeffs):
         assert np.array_equal(g4[0], grad[0][:4])
+
+
+def test_adam_on_aberration_coefficients_matches_oracle(gpu_lib, problem):
+    """Mask bits 4..10: Adam on the Zernike coefficients (theta held) against the
+    oracle's Adam driven by central differences of its loss."""
+    import torch
+    starts, d, etas, nu_c = problem
+    o = starts[2].replace(zernike=ABER)
+    iters, lr_z, bound = 4, 0.01, 0.3
+    print("[case] Adam on aberration coefficients", flush=True)
+    out, loss, _, _ = gpu_lib.autotune([o], torch.from_numpy(d[2:3]).cuda(), etas[2:3], iters=iters,
+                                       lr=LR, lo=LO, hi=HI, mask=0x7F << 4, nu_c=nu_c,
+                                       lr_zernike=lr_z, zernike_bound=bound)
+    c, L = at.autotune_aberration(o, d[2].astype(np.float64), etas[2], nu_c, iters, lr_z, bound)
+    got = np.array(out[0].zernike)
+    print(f"  gpu {got}\n  ora {c}")
+    # theta held, every coefficient moved by about lr per step, as the oracle's
+    assert out[0].defocus == o.defocus and out[0].na_det == o.na_det
+    assert np.all(np.abs(got - c) <= 0.02 * lr_z * iters + 1e-6)
+    assert abs(loss[0] - L) / abs(L) < 1e-3
