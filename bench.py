@@ -190,6 +190,7 @@ def main():
     ap.add_argument("--restore-tiles", type=int, default=64)
     ap.add_argument("--fov-size", type=int, default=2048, help="field of view side (0: skip)")
     ap.add_argument("--no-multi-aperture", action="store_true")
+    ap.add_argument("--no-aberration", action="store_true")
     ap.add_argument("--no-fft-tune", action="store_true", help="keep the default FFT schedules")
     ap.add_argument("--fft-plans", default="", help="import an FFT schedule table instead of tuning")
     ap.add_argument("--save-fft-plans", default="", help="write the FFT schedule table used")
@@ -382,6 +383,8 @@ def main():
 
     if not args.no_multi_aperture:
         out["multi_aperture"] = multi_aperture_section(api, torch, dev, args.steps)
+    if not args.no_aberration:
+        out["aberration"] = aberration_section(api, torch, dev, args.steps)
     if not args.no_autotune:
         net, train = None, None
         if args.cnn_train_patches > 0:
@@ -698,6 +701,45 @@ def fov_section(api, torch, dev, net, cnn_iters, size=2048, nz=32, grid=6, overl
             "fov_per_s": 1.0 / dt, "voxels_per_s": vox / dt, "seconds": round(dt, 3),
             "median_norm_param_err": round(med, 4), "median_norm_err_defocus_na_tilt": per,
             "median_norm_err_defocus_tilt": tuned_err(th, truth)}
+
+
+def aberration_section(api, torch, dev, steps, n_patches=256, iters=20):
+    """Detection aberrations (Zernike Noll 5..11 in the detection pupil, Methods
+    detection-parameter branch): TF synthesis of the bench volume with every
+    coefficient at 0.05 waves, and the auto-tune iteration of the 32x128x128
+    patches with theta only vs theta plus the seven coefficients tuned."""
+    from paper_2412_09775_amd import learned_init
+    Z, Y, X = WORKLOAD["nz"], WORKLOAD["ny"], WORKLOAD["nx"]
+    o = api.Optics(**dict(WORKLOAD, zernike=(0.05,) * 7))
+    tf = api.transfer_function([o], device=dev)
+    ws_tf = torch.empty(api.workspace_size([o], api.OP_TRANSFER_FUNCTION), dtype=torch.uint8, device=dev)
+    api.transfer_function([o], out=tf, ws=ws_tf)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        api.transfer_function([o], out=tf, ws=ws_tf)
+    torch.cuda.synchronize()
+    tf_ms = (time.perf_counter() - t0) * 1e3 / steps
+    del tf, ws_tf
+    tmpl = api.Optics(**TUNE)
+    stacks, _ = learned_init.simulate(tmpl, n_patches, seed=31, device=dev)
+    opts = [api.Optics(**TUNE) for _ in range(n_patches)]
+    eta = 1e-2 * thin_sigma_max_sq(api.transfer_function([tmpl], device=dev))
+    ws = torch.empty(api.tune_workspace_size(opts, 1), dtype=torch.uint8, device=dev)
+    res = {"workload": f"TF synthesis {Z}x{Y}x{X} with 7 Zernike terms at 0.05 waves; auto-tune of "
+                       f"{n_patches} patches 32x128x128, {iters} iterations, graph replay",
+           "tf_ms": tf_ms}
+    for label, mask in (("theta", 0b0101), ("theta_and_zernike", 0b0101 | (0x7F << 4))):
+        kw = dict(iters=iters, mask=mask, use_graph=1, ws=ws, lr_zernike=0.01, zernike_bound=0.5)
+        api.autotune(opts, stacks, eta, **dict(kw, iters=2))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        api.autotune(opts, stacks, eta, **kw)
+        torch.cuda.synchronize()
+        res[f"ms_per_iter_{label}"] = (time.perf_counter() - t0) * 1e3 / iters
+    print(f"[bench] aberrations: TF {tf_ms:.2f} ms; auto-tune {res['ms_per_iter_theta']:.2f} -> "
+          f"{res['ms_per_iter_theta_and_zernike']:.2f} ms/iter", file=sys.stderr, flush=True)
+    return res
 
 
 def multi_aperture_section(api, torch, dev, steps, shape=(48, 512, 512)):
