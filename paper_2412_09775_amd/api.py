@@ -430,7 +430,7 @@ def autotune(optics, d, eta, iters=100, lr=PAPER_LR, lo=(-1e300,) * 4, hi=(1e300
 
 def restore_tiles(optics, d, eta, iters=20, lr=PAPER_LR, lo=(-1e300,) * 4, hi=(1e300,) * 4,
                   mask=0b0111, multistart=1, theta0=None, nu_c=None, use_graph=2, branches=0,
-                  f_out=None, ws=None, stream=None):
+                  f_out=None, ws=None, stream=None, lr_zernike=0.0, zernike_bound=0.0):
     """Auto-tune then thin reconstruction of uneven tiles.  Returns (optics list, loss,
     all_theta, all_loss, f) with f a list of [2, Y_i, X_i] views into one packed buffer."""
     import torch
@@ -441,7 +441,8 @@ def restore_tiles(optics, d, eta, iters=20, lr=PAPER_LR, lo=(-1e300,) * 4, hi=(1
         f_out = torch.empty(sum(sizes), dtype=torch.float32, device=d.device)
     lib = load()
     res = _tune_call(lib.wo_restore_tiles, "wo_restore_tiles", optics, d, eta, iters, lr, lo, hi, mask,
-                     multistart, theta0, nu_c, use_graph, branches, ws, stream, (_ptr(f_out),))
+                     multistart, theta0, nu_c, use_graph, branches, ws, stream, (_ptr(f_out),),
+                     lr_zernike, zernike_bound)
     views, off = [], 0
     for o, sz in zip(optics, sizes):
         views.append(f_out[off:off + sz].view(2, int(_get(o, "ny")), int(_get(o, "nx"))))

@@ -160,3 +160,31 @@ def test_reused_graph_takes_new_parameters(gpu_lib, tiles, mode):
     assert np.array_equal(b1[2], ref[2]) and np.array_equal(b1[1], ref[1])
     for x, y in zip(f1, ref[4]):
         assert np.array_equal(x, y.cpu().numpy())
+
+
+def test_graph_with_aberration_tuning_is_not_reused_for_plain_theta(gpu_lib, tiles):
+    """A whole-call graph captured for theta-only tuning is not replayed for a call
+    that tunes the aberration coefficients with the same shapes and buffers (the
+    aberration-aware kernels differ); both equal their plain-launch results."""
+    import torch
+    starts, stacks, etas, nucs = tiles
+    print("[case] graph keys with aberration tuning", flush=True)
+    d = gpu_lib.pack_stacks(dev(stacks))
+    ws = torch.empty(gpu_lib.tune_workspace_size(starts, 1), dtype=torch.uint8, device="cuda")
+    fo = torch.empty(sum(2 * o.ny * o.nx for o in starts), dtype=torch.float32, device="cuda")
+    kw = dict(iters=3, nu_c=nucs, lr=LR, lo=LO, hi=HI, ws=ws, f_out=fo)
+    zkw = dict(mask=0b0101 | (0x7F << 4), lr_zernike=0.01, zernike_bound=0.3)
+    res = {}
+    for name, extra in (("theta", dict(mask=0b0101)), ("zern", zkw)):
+        for mode in (2, 0):
+            r = gpu_lib.restore_tiles(starts, d, etas, use_graph=mode, **kw, **extra)
+            res[(name, mode)] = (r[1].copy(), [np.array(o.zernike) for o in r[0]],
+                                 [x.cpu().numpy() for x in r[4]])
+    for name in ("theta", "zern"):
+        a, b = res[(name, 2)], res[(name, 0)]
+        assert np.array_equal(a[0], b[0])
+        for x, y in zip(a[2], b[2]):
+            assert np.array_equal(x, y)
+    # the aberration call moved the coefficients, the theta-only call did not
+    assert all(np.any(z != 0) for z in res[("zern", 0)][1])
+    assert all(len(z) == 0 or not np.any(z) for z in res[("theta", 0)][1])
