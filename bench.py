@@ -65,7 +65,7 @@ CSRC = os.path.join(ROOT, "paper_2412_09775_amd", "csrc")
 # column passes share one symbol across launches and are not listed)
 COUNTER_NAMES = {"k_zop<2>": "wo::k_zop<2, 1, 96>", "k_rows_r2c": "wo::k_rows_r2c<512>",
                  "k_rows_c2r": "wo::k_rows_c2r<512>", "k_tf_rows_lf": "wo::k_tf_rows_lf<512>",
-                 "k_tf_fields_y": "wo::k_tf_fields_y<512, 2>"}
+                 "k_tf_fields_y": "wo::k_tf_fields_y<512, 2, false>"}
 
 
 def source_sha1():
