@@ -36,25 +36,32 @@ WORKLOAD = dict(model=1, nz=96, ny=512, nx=512, dz=0.2, dy=0.1, dx=0.1, waveleng
 ETA_REL = 1e-3
 
 
-def kernel_bytes(name, Z, Y, X, C=1, P=2):
-    """Algorithmic HBM bytes one launch of each kernel must move in this step."""
+def kernel_bytes(name, Z, Y, X, sup, C=1, P=2):
+    """Algorithmic HBM bytes one launch of each kernel must move in this step.
+
+    sup = (field columns, bank half-spectrum columns kt, band rows nb) of the
+    lateral support (wo_lateral_support): the fields are kept on the detection
+    pupil's columns, the bank and the spectra on the columns k < kt of every row
+    (of the band rows once transformed along Y)."""
+    fc, kt, nb = sup
     Xh = X // 2 + 1
     cplx = 8
-    half = Z * Y * Xh
     full = Z * Y * X
+    rows_kt = Z * Y * kt          # compact half spectrum, every row
+    band = Z * nb * kt            # compact half spectrum, band rows
     table = {
         # reconstruction
-        "k_rows_r2c": C * (4 * full + cplx * half),
-        "k_cols_y_fwd": C * 2 * cplx * half,
-        f"k_zop<{P}>": cplx * half * (C + C * P + P),
-        "k_cols_y_inv": P * 2 * cplx * half,
-        "k_rows_c2r": P * (cplx * half + 4 * full),
+        "k_rows_r2c": C * (4 * full + cplx * rows_kt),
+        "k_cols_y_fwd": C * cplx * (rows_kt + band),
+        f"k_zop<{P}>": cplx * band * (C + C * P + P),
+        "k_cols_y_inv": P * cplx * (band + rows_kt),
+        "k_rows_c2r": P * (cplx * rows_kt + 4 * full),
         # transfer-function synthesis
-        "k_pupil_sums": 0,
-        "k_tf_fields_y": 2 * cplx * full,
-        "k_tf_rows_lf": 2 * cplx * full + 2 * cplx * half,
-        "k_cols_y_tf": 2 * 2 * cplx * half,
-        "k_cols_z_tf": 2 * 2 * cplx * half,
+        "k_tf_fields_y": 2 * cplx * Z * Y * fc,
+        "k_tf_rows_lf": 2 * cplx * Z * Y * fc + 2 * cplx * rows_kt,
+        "k_cols_y_tf": 2 * 2 * cplx * rows_kt,
+        # band rows' Z transform, plus the zeros of the rest of the bank
+        "k_cols_expand": 2 * 2 * cplx * band + 2 * cplx * (Z * Y * Xh - band),
     }
     return table.get(name)
 
@@ -65,7 +72,8 @@ CSRC = os.path.join(ROOT, "paper_2412_09775_amd", "csrc")
 # column passes share one symbol across launches and are not listed)
 COUNTER_NAMES = {"k_zop<2>": "wo::k_zop<2, 1, 96>", "k_rows_r2c": "wo::k_rows_r2c<512>",
                  "k_rows_c2r": "wo::k_rows_c2r<512>", "k_tf_rows_lf": "wo::k_tf_rows_lf<512>",
-                 "k_tf_fields_y": "wo::k_tf_fields_y<512, 2, false>"}
+                 "k_tf_fields_y": "wo::k_tf_fields_y<512, 2, false>",
+                 "k_cols_expand": "wo::k_cols_expand<96, 16>"}
 
 
 def source_sha1():
@@ -230,6 +238,7 @@ def main():
     o = api.Optics(**WORKLOAD)
     Z, Y, X = o.nz, o.ny, o.nx
     V = Z * Y * X
+    sup = api.lateral_support([o])
 
     # ---- inputs (untimed): specimen, forward model on the GPU, noise on the host
     t0 = time.time()
@@ -345,15 +354,17 @@ def main():
     ms_rec = (time.perf_counter() - r0) * 1e3 / args.steps
 
     kernels = {}
+    step_bytes = 0
     for name, (cnt, tot) in sorted(kern.items()):
         per = tot / cnt
-        b = kernel_bytes(name, Z, Y, X)
+        b = kernel_bytes(name, Z, Y, X, sup)
         ent = {"launches": cnt, "avg_ms": round(per, 5)}
         if b:
             ent["alg_bytes"] = b
             ent["alg_GBps"] = round(b / (per * 1e-3) / 1e9, 1)
+            step_bytes += b * cnt // args.steps
         kernels[name] = ent
-    dom_b = kernel_bytes(dom, Z, Y, X) or 0
+    dom_b = kernel_bytes(dom, Z, Y, X, sup) or 0
     dom_ms = dom_rec[1] / dom_rec[0]
     ach = dom_b / (dom_ms * 1e-3) / 1e9
     roof = {"kernel": dom, "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
@@ -375,9 +386,14 @@ def main():
         "data": "synthetic",
         "config": {"workload": "label-free 3D phase+absorption, 96x512x512, 1 channel x 2 properties",
                    "shape_zyx": [Z, Y, X], "voxel_um": [o.dz, o.dy, o.dx], "eta_rel": ETA_REL},
+        "lateral_support": {"field_cols": sup[0], "tf_cols": sup[1], "band_rows": sup[2]},
         "reconstruct_cached_tf": {"ms": ms_rec, "voxels_per_s": V / (ms_rec * 1e-3)},
         "fft_schedules": tuner,
         "roofline": roof,
+        # every library kernel of the step: algorithmic bytes per step over the
+        # timed step duration (launch gaps and all)
+        "step_hbm": {"alg_bytes": step_bytes, "GBps": round(step_bytes / (ms * 1e-3) / 1e9, 1),
+                     "frac": round(step_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
         "kernels": kernels,
     }
 
@@ -776,13 +792,13 @@ def multi_aperture_section(api, torch, dev, steps, shape=(48, 512, 512)):
     api.timing_enable(False)
     kern = api.timing_report()
     V = Z * Y * X
-    H = Z * Y * (X // 2 + 1)
     zop = kern.get("k_zop<1>")
     res = {"workload": f"9 apertures x phase, {Z}x{Y}x{X}", "tf_ms": (t1 - t0) * 1e3 / steps,
            "reconstruct_ms": (t2 - t1) * 1e3 / steps, "reconstruct_voxels_per_s": V * steps / (t2 - t1)}
     if zop:
         per = zop[1] / zop[0]
-        b = 8 * H * (9 + 9 + 1)
+        _, kt, nb = api.lateral_support([o])
+        b = 8 * Z * nb * kt * (9 + 9 + 1)
         res["k_zop<1>"] = {"avg_ms": round(per, 5), "alg_bytes": b, "alg_GBps": round(b / (per * 1e-3) / 1e9, 1)}
     print(f"[bench] multi-aperture: TF {res['tf_ms']:.2f} ms, reconstruct {res['reconstruct_ms']:.2f} ms",
           file=sys.stderr, flush=True)

@@ -135,9 +135,27 @@ size_t wo_workspace_size(const wo_optics* o, int32_t n, int32_t op);
 int wo_transfer_function(const wo_optics* o, int32_t n, void* tf_out, void* ws, size_t ws_bytes,
                          void* stream);
 
+/* Lateral support of the model's fields and transfer-function bank for n
+ * patches (Methods, pupils): the detection pupil is zero beyond NA_det/lambda0
+ * and the source beyond its tilted disc of radius NA_ill/lambda0 (each widened
+ * by the soft edge), so the label-free fields vanish outside the detection
+ * pupil's columns, the bank outside the sum of the two supports (twice the
+ * detection pupil's for fluorescence).  *field_cols: columns of the fields
+ * kept by the transfer-function synthesis (nx: all); *tf_cols: the bank's
+ * half-spectrum columns k < tf_cols that can be nonzero; *band_rows: its rows
+ * y <= ky or y >= ny - ky, band_rows = 2 ky + 1 (ny: all rows).  Bounds keep one
+ * spare column or row and are rounded up to multiples of 16.  The 3D linear
+ * calls (wo_forward, wo_reconstruct, wo_adjoint) read the bank only there and
+ * take it as zero elsewhere, as wo_transfer_function writes it.  Outputs may
+ * be NULL. */
+int wo_lateral_support(const wo_optics* o, int32_t n, int32_t* field_cols, int32_t* tf_cols,
+                       int32_t* band_rows);
+
 /* Forward model D_c = sum_p H_cp F_p + N b_c delta(nu), d_c = IFFT(D_c)
  * (Methods, "Linear contrast-separable shift-invariant imaging systems").
- * tf: bank from wo_transfer_function (or any Hermitian bank of that layout);
+ * tf: bank from wo_transfer_function, or any Hermitian bank of that layout
+ * that vanishes outside the model's lateral support (wo_lateral_support; the
+ * 3D models do not read it there);
  * f: [n][P][vol], b: [n][C] or NULL, d_out: [n][C][vol]; vol = nz*ny*nx
  * (3D) or ny*nx for the thin model's object. */
 int wo_forward(const wo_optics* o, int32_t n, const void* tf, const float* f, const float* b,

@@ -38,7 +38,8 @@ SYMBOLS = ("wo_bank_shape", "wo_workspace_size", "wo_transfer_function", "wo_for
            "wo_cnn_train_step", "wo_conv3d_forward", "wo_conv3d_input_grad", "wo_conv3d_weight_grad",
            "wo_synth_thin_cells", "wo_add_gaussian_noise", "wo_crop_stacks", "wo_fft_tune",
            "wo_fft_plans_export", "wo_fft_plans_import", "wo_fft_plans_clear", "wo_fft_candidates",
-           "wo_tile_grid", "wo_stitch_tiles", "wo_timing_select", "wo_midband_loss_grad_aberration")
+           "wo_tile_grid", "wo_stitch_tiles", "wo_timing_select", "wo_midband_loss_grad_aberration",
+           "wo_lateral_support")
 
 _FIELDS = ("model", "nz", "ny", "nx", "dz", "dy", "dx", "wavelength", "na_ill", "na_det",
            "n_medium", "defocus", "tilt_zenith", "tilt_azimuth", "edge_width", "swing")
@@ -110,6 +111,8 @@ def load(path: str = LIB_PATH):
                                   ctypes.POINTER(ctypes.c_int64)]
     lib.wo_workspace_size.argtypes = [op, i32, i32]
     lib.wo_workspace_size.restype = sz
+    lib.wo_lateral_support.argtypes = [op, i32, ctypes.POINTER(i32), ctypes.POINTER(i32),
+                                       ctypes.POINTER(i32)]
     lib.wo_transfer_function.argtypes = [op, i32, vp, vp, sz, vp]
     lib.wo_forward.argtypes = [op, i32, vp, vp, vp, vp, vp, sz, vp]
     lib.wo_reconstruct.argtypes = [op, i32, vp, vp, vp, ctypes.c_double, vp, vp, sz, vp]
@@ -194,6 +197,17 @@ def bank_shape(optics):
     _check(lib.wo_bank_shape(arr, ctypes.byref(C), ctypes.byref(P), ctypes.byref(dims), ctypes.byref(n)),
            "wo_bank_shape")
     return C.value, P.value, dims.value, n.value
+
+
+def lateral_support(optics):
+    """(field columns, bank half-spectrum columns, band rows) of the model's lateral
+    support for these patches (wo_lateral_support)."""
+    lib = load()
+    arr = optics_array(optics)
+    fc, tc, br = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    _check(lib.wo_lateral_support(arr, len(arr), ctypes.byref(fc), ctypes.byref(tc), ctypes.byref(br)),
+           "wo_lateral_support")
+    return fc.value, tc.value, br.value
 
 
 def workspace_size(optics, op: int) -> int:

@@ -277,6 +277,55 @@ size_t partials_bytes(const wo_optics* o, int32_t n) {
 // Field sets the TF synthesis generates per patch: one per illumination aperture.
 int field_sets(const wo_optics* o) { return o->model == WO_MODEL_SECTORS9_3D ? 9 : 1; }
 
+// Lateral support of the fields and transfer functions of n patches
+// (Methods, pupils): the detection pupil P is zero for |p| > NA_det/lambda0,
+// the source S outside its tilted disc of radius NA_ill/lambda0, each widened
+// by the soft edge.  The label-free fields A = S P e^{..} and B = P g e^{..}
+// therefore vanish outside the columns and rows of P's support, and the
+// transfer function, their correlation, outside the sum of the supports of A
+// and B; the fluorescence OTF, the autocorrelation of P's field, outside
+// twice P's support.  No wrap-around: the aliasing check keeps these sums
+// below Nyquist.  Each bound keeps one spare column or row; compact widths
+// are multiples of 16.
+LatSupport lateral_support(const wo_optics* o, int32_t n) {
+  const Sampling sm = sampling_of(o);
+  LatSupport ls = full_support(sm);
+  const int X = o->nx, Y = o->ny, Xh = X / 2 + 1;
+  const double fx1 = 1.0 / (X * o->dx), fy1 = 1.0 / (Y * o->dy);
+  const double dnu = fmin(fx1, fy1);
+  int px = 0, py = 0, ax = 0, ay = 0;
+  for (int i = 0; i < n; ++i) {
+    const double hw = o[i].edge_width * dnu;
+    const double rd = o[i].na_det / o[i].wavelength + hw;
+    const double ri = o[i].na_ill / o[i].wavelength + hw;
+    const double r = o[i].n_medium * sin(o[i].tilt_zenith) / o[i].wavelength;
+    const double cy = fabs(r * sin(o[i].tilt_azimuth)), cx = fabs(r * cos(o[i].tilt_azimuth));
+    // optics the library would reject (or a pupil wider than the grid) keep
+    // the full layout
+    const double qx = rd / fx1, qy = rd / fy1, sx = (cx + ri) / fx1, sy = (cy + ri) / fy1;
+    if (!(qx >= 0.0 && qx < X && qy >= 0.0 && qy < Y && sx >= 0.0 && sy >= 0.0)) return ls;
+    const int bx = (int)floor(qx) + 1, by = (int)floor(qy) + 1;
+    px = std::max(px, bx);
+    py = std::max(py, by);
+    if (o->model == WO_MODEL_FLUOR_3D) {
+      ax = px;
+      ay = py;
+    } else {
+      ax = std::max(ax, std::min(bx, sx < X ? (int)floor(sx) + 1 : bx));
+      ay = std::max(ay, std::min(by, sy < Y ? (int)floor(sy) + 1 : by));
+    }
+  }
+  const int xc = (2 * px + 1 + 15) / 16 * 16;
+  if (xc < X) {
+    ls.xc = xc;
+    ls.kp = px;
+  }
+  const int kt = (px + ax + 1 + 15) / 16 * 16;
+  if (kt < Xh) ls.kt = kt;
+  if (2 * (py + ay) + 1 < Y) ls.ky = py + ay;
+  return ls;
+}
+
 size_t tf_ws(const wo_optics* o, int32_t n, const Shape& s) {
   const int nf = o->model == WO_MODEL_FLUOR_3D ? 1 : 2;
   const int nv = n * field_sets(o);
@@ -307,20 +356,35 @@ int run_linear(const wo_optics* o, int32_t n, const Shape& s, const float2* tf, 
   const long zd = s.thin ? 1 : s.Z;
   float2* spec = (float2*)ws;
   const long M = s.Y * s.Xh;
-  RowGroups gin{cin * zd * s.Y, cin * zd * s.Y, CH * zd * s.Y, n};
-  WO_TRY(launch_rows_r2c(in, spec, (int)s.X, gin, st));
-  WO_TRY(launch_cols(spec, (int)s.Y, s.Xh, cin * zd, CH * zd, n, -1.f, st, "k_cols_y_fwd"));
   const double nfull = s.thin ? (double)s.Y * s.X : (double)s.Z * s.Y * s.X;
   const float inv_n = (float)(1.0 / nfull);
+  RowGroups gin{cin * zd * s.Y, cin * zd * s.Y, CH * zd * s.Y, n};
+  RowGroups gout{cout * zd * s.Y, CH * zd * s.Y, cout * zd * s.Y, n};
+  const LatSupport sup = s.thin ? full_support(sampling_of(o)) : lateral_support(o, n);
+  if (!s.thin && (sup.kt < s.Xh || sup.ky < s.Y)) {
+    // The bank vanishes outside the transfer function's lateral support, and
+    // so do the forward model's spectrum (but for its DC background term), the
+    // Tikhonov solution and the adjoint: the spectra are kept as the columns
+    // k < kt of every row (stored for the band rows only) and the Z pass
+    // covers the band.
+    const int kt = sup.kt, ky = sup.ky;
+    const SpecBand band{(int)s.Y, kt, ky};
+    WO_TRY(launch_rows_r2c(in, spec, (int)s.X, gin, st, kt, kt));
+    WO_TRY(launch_cols(spec, (int)s.Y, kt, cin * zd, CH * zd, n, -1.f, st, "k_cols_y_fwd", 1, ky));
+    WO_TRY(launch_zop(spec, tf, s.C, s.P, (int)s.Z, M, CH, n, mode, eta, bg, inv_n, nfull, st, &band));
+    WO_TRY(launch_cols(spec, (int)s.Y, kt, cout * zd, CH * zd, n, 1.f, st, "k_cols_y_inv", 2, ky));
+    WO_TRY(launch_rows_c2r(spec, out, (int)s.X, gout, 1.f, st, kt, kt));
+    return WO_OK;
+  }
+  WO_TRY(launch_rows_r2c(in, spec, (int)s.X, gin, st));
+  WO_TRY(launch_cols(spec, (int)s.Y, s.Xh, cin * zd, CH * zd, n, -1.f, st, "k_cols_y_fwd"));
   if (s.thin) {
     WO_TRY(launch_op2d(spec, tf, s.C, s.P, M, CH, n, mode, eta, bg, inv_n, nfull, st));
   } else {
     WO_TRY(launch_zop(spec, tf, s.C, s.P, (int)s.Z, M, CH, n, mode, eta, bg, inv_n, nfull, st));
   }
   WO_TRY(launch_cols(spec, (int)s.Y, s.Xh, cout * zd, CH * zd, n, 1.f, st, "k_cols_y_inv"));
-  RowGroups gout{cout * zd * s.Y, CH * zd * s.Y, cout * zd * s.Y, n};
   WO_TRY(launch_rows_c2r(spec, out, (int)s.X, gout, 1.f, st));
-  (void)o;
   return WO_OK;
 }
 
@@ -942,6 +1006,18 @@ size_t wo_workspace_size(const wo_optics* o, int32_t n, int32_t op) {
   return 0;
 }
 
+int wo_lateral_support(const wo_optics* o, int32_t n, int32_t* field_cols, int32_t* tf_cols,
+                       int32_t* band_rows) {
+  int st = validate(o, n);
+  if (st) return st;
+  const LatSupport ls = lateral_support(o, n);
+  const int nb = ls.ky >= o->ny ? o->ny : 2 * ls.ky + 1;
+  if (field_cols) *field_cols = o->model == WO_MODEL_FLUOR_3D ? o->nx : ls.xc;
+  if (tf_cols) *tf_cols = ls.kt;
+  if (band_rows) *band_rows = nb;
+  return WO_OK;
+}
+
 int wo_transfer_function(const wo_optics* o, int32_t n, void* tf_out, void* ws, size_t ws_bytes,
                          void* stream) {
   int st = validate(o, n);
@@ -972,10 +1048,26 @@ int wo_transfer_function(const wo_optics* o, int32_t n, void* tf_out, void* ws, 
   WO_TRY(launch_set_params(dopt, h.data(), nv, hs));
   Sampling sm = sampling_of(o);
   for (int i = 0; i < n; ++i) sm.aberrated |= aberrated(o[i]) ? 1 : 0;
-  WO_TRY(launch_tf_fields_y(dopt, sm, nv, ab, partials, hs));
+  // The label-free models compute and store only the columns of the
+  // detection pupil's support; the 3D ones also keep the transfer function
+  // in its support (columns kx < kt, band rows) until the Z pass, which
+  // writes the full bank (zeros outside), when that compact copy fits the
+  // field buffer behind the compact fields.
+  LatSupport sup = o->model == WO_MODEL_FLUOR_3D ? full_support(sm) : lateral_support(o, n);
+  WO_TRY(launch_tf_fields_y(dopt, sm, nv, ab, partials, hs, &sup));
   float2* tf = (float2*)tf_out;
   const long M = s.Y * s.Xh;
   const long plane = s.Y * s.Xh;
+  const long fields = (long)nv * nf * s.Z * s.Y * sup.xc;
+  const long cplane = s.Y * (long)sup.kt;
+  const int P3 = o->model == WO_MODEL_SECTORS9_3D ? 1 : 2;
+  float2* cb = ab + (fields + 31) / 32 * 32;
+  const bool compact_out = (o->model == WO_MODEL_LABELFREE_3D || o->model == WO_MODEL_SECTORS9_3D) &&
+                           (sup.kt < s.Xh || sup.ky < s.Y) &&
+                           (fields + 31) / 32 * 32 + (long)nv * P3 * s.Z * cplane <=
+                               (long)nv * nf * s.Z * s.Y * s.X;
+  LatSupport full_out = sup;
+  full_out.kt = (int)s.Xh;
   switch (o->model) {
     case WO_MODEL_FLUOR_3D:
       WO_TRY(launch_tf_rows_fluor(partials, sm, n, ab, tf, hs));
@@ -983,23 +1075,40 @@ int wo_transfer_function(const wo_optics* o, int32_t n, void* tf_out, void* ws, 
       WO_TRY(launch_cols(tf, (int)s.Z, M, 1, 1, n, -1.f, hs, "k_cols_z_tf"));
       break;
     case WO_MODEL_LABELFREE_3D:
-      WO_TRY(launch_tf_rows_labelfree(partials, sm, n, ab, tf, 2 * s.Z * plane, s.Z * plane, plane, hs));
-      WO_TRY(launch_cols(tf, (int)s.Y, s.Xh, 2 * s.Z, 2 * s.Z, n, -1.f, hs, "k_cols_y_tf"));
-      WO_TRY(launch_cols(tf, (int)s.Z, M, 2, 2, n, -1.f, hs, "k_cols_z_tf"));
+      if (compact_out) {
+        WO_TRY(launch_tf_rows_labelfree(partials, sm, n, ab, cb, 2 * s.Z * cplane, s.Z * cplane, cplane,
+                                        hs, &sup, sup.kt));
+        WO_TRY(launch_cols(cb, (int)s.Y, sup.kt, 2 * s.Z, 2 * s.Z, n, -1.f, hs, "k_cols_y_tf", 1, sup.ky));
+        WO_TRY(launch_cols_expand(cb, tf, (int)s.Z, (int)s.Y, (int)s.Xh, sup.kt, sup.ky, 2L * n, -1.f, hs));
+      } else {
+        WO_TRY(launch_tf_rows_labelfree(partials, sm, n, ab, tf, 2 * s.Z * plane, s.Z * plane, plane, hs,
+                                        &full_out));
+        WO_TRY(launch_cols(tf, (int)s.Y, s.Xh, 2 * s.Z, 2 * s.Z, n, -1.f, hs, "k_cols_y_tf"));
+        WO_TRY(launch_cols(tf, (int)s.Z, M, 2, 2, n, -1.f, hs, "k_cols_z_tf"));
+      }
       break;
     case WO_MODEL_LABELFREE_THIN:
-      WO_TRY(launch_tf_rows_labelfree(partials, sm, n, ab, tf, 2 * s.Z * plane, plane, 2 * plane, hs));
+      WO_TRY(launch_tf_rows_labelfree(partials, sm, n, ab, tf, 2 * s.Z * plane, plane, 2 * plane, hs,
+                                      &full_out));
       WO_TRY(launch_cols(tf, (int)s.Y, s.Xh, 2 * s.Z, 2 * s.Z, n, -1.f, hs, "k_cols_y_tf"));
       break;
     case WO_MODEL_SECTORS9_3D:
       // phase TF of every aperture: [patch][aperture][1][Z][Y][Xh]
-      WO_TRY(launch_tf_rows_labelfree(partials, sm, nv, ab, tf, s.Z * plane, -1, plane, hs));
-      WO_TRY(launch_cols(tf, (int)s.Y, s.Xh, s.Z, s.Z, nv, -1.f, hs, "k_cols_y_tf"));
-      WO_TRY(launch_cols(tf, (int)s.Z, M, 1, 1, nv, -1.f, hs, "k_cols_z_tf"));
+      if (compact_out) {
+        WO_TRY(launch_tf_rows_labelfree(partials, sm, nv, ab, cb, s.Z * cplane, -1, cplane, hs, &sup,
+                                        sup.kt));
+        WO_TRY(launch_cols(cb, (int)s.Y, sup.kt, s.Z, s.Z, nv, -1.f, hs, "k_cols_y_tf", 1, sup.ky));
+        WO_TRY(launch_cols_expand(cb, tf, (int)s.Z, (int)s.Y, (int)s.Xh, sup.kt, sup.ky, nv, -1.f, hs));
+      } else {
+        WO_TRY(launch_tf_rows_labelfree(partials, sm, nv, ab, tf, s.Z * plane, -1, plane, hs, &full_out));
+        WO_TRY(launch_cols(tf, (int)s.Y, s.Xh, s.Z, s.Z, nv, -1.f, hs, "k_cols_y_tf"));
+        WO_TRY(launch_cols(tf, (int)s.Z, M, 1, 1, nv, -1.f, hs, "k_cols_z_tf"));
+      }
       break;
     case WO_MODEL_POL5_3D: {
       float2* uw = (float2*)w;
-      WO_TRY(launch_tf_rows_labelfree(partials, sm, n, ab, uw, 2 * s.Z * plane, s.Z * plane, plane, hs));
+      WO_TRY(launch_tf_rows_labelfree(partials, sm, n, ab, uw, 2 * s.Z * plane, s.Z * plane, plane, hs,
+                                      &full_out));
       WO_TRY(launch_cols(uw, (int)s.Y, s.Xh, 2 * s.Z, 2 * s.Z, n, -1.f, hs, "k_cols_y_tf"));
       WO_TRY(launch_tf_pol5_z(dopt, sm, n, uw, tf, hs));
       break;

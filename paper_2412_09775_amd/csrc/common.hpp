@@ -523,6 +523,26 @@ __host__ __device__ __forceinline__ double fftfreq(int k, int n, double d) {
   return (double)ks * val;
 }
 
+// e / d for 0 <= e < 2^20 and 1 <= d <= 2^13, given inv_d = 1.0f / d: the exact
+// quotient of e + 0.5 lies at least 0.5 / d from an integer, far more than the
+// rounding error of the float product (a runtime integer division costs
+// dozens of instructions per element).
+__device__ __forceinline__ int div_small(int e, float inv_d) {
+  return (int)(((float)e + 0.5f) * inv_d);
+}
+
+// Compact column layout of a band-limited lateral axis: of the X frequency
+// columns only kx <= KP (zero and positive frequencies) and the XC - KP - 1
+// highest (negative frequencies) are stored; column c holds kx = c for
+// c <= KP and kx = c + X - XC beyond.  XC = X with KP = X - 1 is the plain
+// layout.  compact_column is the inverse (-1: a column that is not stored).
+__host__ __device__ __forceinline__ int field_column(int c, int KP, int X, int XC) {
+  return c <= KP ? c : c + (X - XC);
+}
+__host__ __device__ __forceinline__ int compact_column(int kx, int KP, int X, int XC) {
+  return kx <= KP ? kx : (kx >= X - (XC - KP - 1) ? kx - (X - XC) : -1);
+}
+
 __host__ __device__ __forceinline__ double edge_profile(double inside, double hw) {
   if (hw == 0.0) return inside >= 0.0 ? 1.0 : 0.0;
   double t = (inside / hw + 1.0) * 0.5;

@@ -20,7 +20,8 @@ __device__ __forceinline__ long group_row(long r, long rpg, long stride) {
 template <int NS>
 __global__ __launch_bounds__(1024) void k_rows_r2c(const float* __restrict__ in,
                                                    float2* __restrict__ out, int X, RowGroups g,
-                                                   FftPlan plan, int lines_per_wg, long nlines) {
+                                                   FftPlan plan, int lines_per_wg, long nlines,
+                                                   int KT, int OP) {
   extern __shared__ float2 smem[];
   float2* tw = smem;
   float2* buf = smem + X;
@@ -63,18 +64,19 @@ __global__ __launch_bounds__(1024) void k_rows_r2c(const float* __restrict__ in,
     fft_lines<NS, 0, false, kEmax, true>(buf, LdsLines{nl, 1, LS, false, -1, true}, plan, tw, -1.f, tid,
                                          nthr);
   }
-  const int Xh = Xc / 2 + 1;
+  // half-spectrum columns k < KT (all Xh, or the band a caller keeps), row pitch OP
+  const float inv_kt = 1.0f / (float)KT;
 #pragma unroll
   for (int i = 0; i < kEmax; ++i) {
     const int e = tid + i * nthr;
-    if (e < nl * Xh) {
-      const int l = e / Xh, k = e - l * Xh;
+    if (e < nl * KT) {
+      const int l = div_small(e, inv_kt), k = e - l * KT;
       const float2 zk = buf[l * LS + row_slot(k, PS)];
       const float2 zm = buf[l * LS + row_slot(k == 0 ? 0 : Xc - k, PS)];
       const float2 A = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y));
       const float2 B = make_float2(0.5f * (zk.y + zm.y), -0.5f * (zk.x - zm.x));
-      out[rout[2 * l] * Xh + k] = A;
-      if (rout[2 * l + 1] >= 0) out[rout[2 * l + 1] * Xh + k] = B;
+      out[rout[2 * l] * OP + k] = A;
+      if (rout[2 * l + 1] >= 0) out[rout[2 * l + 1] * OP + k] = B;
     }
   }
 }
@@ -83,7 +85,7 @@ template <int NS>
 __global__ __launch_bounds__(1024) void k_rows_c2r(const float2* __restrict__ in,
                                                    float* __restrict__ out, int X, RowGroups g,
                                                    FftPlan plan, int lines_per_wg, long nlines,
-                                                   float scale) {
+                                                   float scale, int KT, int IP) {
   extern __shared__ float2 smem[];
   float2* tw = smem;
   float2* buf = smem + X;
@@ -99,18 +101,23 @@ __global__ __launch_bounds__(1024) void k_rows_c2r(const float2* __restrict__ in
   }
   __syncthreads();
   const int Xc = NS > 0 ? NS : X;   // compile-time length for the index arithmetic
-  const int Xh = Xc / 2 + 1;
   const int PS = pad_shift(Xc);   // row padding
   const int LS = row_stride(Xc);    // padded line pitch in LDS
   auto slot = [&](int e) {
     const int l = e / Xc;
     return l * LS + row_slot(e - l * Xc, PS);
   };
+  // input rows of pitch IP hold the half-spectrum columns k < KT; the
+  // columns beyond are zero (the condition depends on the index only, so the
+  // loads stay in flight together)
   auto load = [&](int l, int k) {
     const int kk = 2 * k > Xc ? Xc - k : k;
     const long ra = rin[2 * l], rb = rin[2 * l + 1];
-    const float2 A = in[ra * Xh + kk];
-    const float2 B = in[(rb >= 0 ? rb : ra) * Xh + kk];
+    float2 A = make_float2(0.f, 0.f), B = A;
+    if (kk < KT) {
+      A = in[ra * IP + kk];
+      B = in[(rb >= 0 ? rb : ra) * IP + kk];
+    }
     return make_float4(A.x, A.y, B.x, B.y);
   };
   auto finish = [&](int l, int k, float4 v) {
@@ -197,10 +204,14 @@ static FftChoice rows_choice(const FftKey& k) {
     hipLaunchKernelGGL((K<NN>), dim3((unsigned)nwg), dim3(thr), lds, s, WO_ROWS_ARGS);          \
     return hipGetLastError();
 
-hipError_t launch_rows_r2c(const float* in, float2* out, int X, const RowGroups& g, hipStream_t s) {
+hipError_t launch_rows_r2c(const float* in, float2* out, int X, const RowGroups& g, hipStream_t s,
+                           int kt, int pitch) {
+  const int Xh = X / 2 + 1;
+  const int KT = kt > 0 ? kt : Xh, OP = pitch > 0 ? pitch : Xh;
+  if (KT > Xh || OP < KT) return hipErrorInvalidValue;
   const long nrows = g.rows_per_group * g.ngroups;
   const FftKey key{kFftRowsR2C, X, 0, nrows, 0};
-  if (fft_recording()) fft_record(key, [=] { return launch_rows_r2c(in, out, X, g, s); });
+  if (fft_recording()) fft_record(key, [=] { return launch_rows_r2c(in, out, X, g, s, KT, OP); });
   const FftChoice c = rows_choice(key);
   FftPlan plan;
   if (!make_plan_variant(X, c.plan, &plan)) return hipErrorInvalidValue;
@@ -210,7 +221,7 @@ hipError_t launch_rows_r2c(const float* in, float2* out, int X, const RowGroups&
   const int thr = c.threads;
   const size_t lds = (size_t)(X + (long)L * row_stride(X)) * sizeof(float2);
   ScopedTiming _t("k_rows_r2c", s);
-#define WO_ROWS_ARGS in, out, X, g, plan, L, nlines
+#define WO_ROWS_ARGS in, out, X, g, plan, L, nlines, KT, OP
 #define X_(NN) WO_CASE_ROWS(k_rows_r2c, NN)
   if (c.plan == 0) switch (X) {
       WO_LATERAL_SIZES(X_)
@@ -224,10 +235,13 @@ hipError_t launch_rows_r2c(const float* in, float2* out, int X, const RowGroups&
 }
 
 hipError_t launch_rows_c2r(const float2* in, float* out, int X, const RowGroups& g, float scale,
-                           hipStream_t s) {
+                           hipStream_t s, int kt, int pitch) {
+  const int Xh = X / 2 + 1;
+  const int KT = kt > 0 ? kt : Xh, IP = pitch > 0 ? pitch : Xh;
+  if (KT > Xh || IP < KT) return hipErrorInvalidValue;
   const long nrows = g.rows_per_group * g.ngroups;
   const FftKey key{kFftRowsC2R, X, 0, nrows, 0};
-  if (fft_recording()) fft_record(key, [=] { return launch_rows_c2r(in, out, X, g, scale, s); });
+  if (fft_recording()) fft_record(key, [=] { return launch_rows_c2r(in, out, X, g, scale, s, KT, IP); });
   const FftChoice c = rows_choice(key);
   FftPlan plan;
   if (!make_plan_variant(X, c.plan, &plan)) return hipErrorInvalidValue;
@@ -237,7 +251,7 @@ hipError_t launch_rows_c2r(const float2* in, float* out, int X, const RowGroups&
   const int thr = c.threads;
   const size_t lds = (size_t)(X + (long)L * row_stride(X)) * sizeof(float2);
   ScopedTiming _t("k_rows_c2r", s);
-#define WO_ROWS_ARGS in, out, X, g, plan, L, nlines, scale
+#define WO_ROWS_ARGS in, out, X, g, plan, L, nlines, scale, KT, IP
 #define X_(NN) WO_CASE_ROWS(k_rows_c2r, NN)
   if (c.plan == 0) switch (X) {
       WO_LATERAL_SIZES(X_)
@@ -252,10 +266,22 @@ hipError_t launch_rows_c2r(const float2* in, float* out, int X, const RowGroups&
 
 // ------------------------------------------------------------------ columns
 
+// Band rows of a compact plane: index b of the nb = 2 ky + 1 band rows is row b
+// (b <= ky) or row Y - nb + b; nb = Y (ky >= Y) is every row.
+__device__ __forceinline__ int band_row(int b, int ky, int nb, int Y) {
+  return b <= ky ? b : b + (Y - nb);
+}
+__device__ __forceinline__ bool in_band(int y, int ky, int nb, int Y) {
+  return nb == Y || y <= ky || y >= Y - (nb - ky - 1);
+}
+
+// band: 0 every row; 1 stores only the band rows (ky, nb) of the transform;
+// 2 loads only the band rows (the others are taken as zero).
 template <int NS, int WS>
 __global__ __launch_bounds__(1024) void k_cols(float2* __restrict__ data, int N, long M, int Wrt,
                                                long tiles_m, long planes_per_group,
-                                               long group_stride, FftPlan plan, float sign) {
+                                               long group_stride, FftPlan plan, float sign,
+                                               int band, int ky, int nb) {
   const int W = WS > 0 ? WS : Wrt;             // a power of two
   const int wsh = WS > 0 ? pow2_shift(WS) : pow2_shift(Wrt);
   extern __shared__ float2 smem[];
@@ -270,26 +296,28 @@ __global__ __launch_bounds__(1024) void k_cols(float2* __restrict__ data, int N,
   const long m0 = tile * W;
   const int weff = (int)min((long)W, M - m0);
   const int Nc = NS > 0 ? NS : N;
+  auto ld_ok = [&](int l, int n) { return l < weff && (band != 2 || in_band(n, ky, nb, Nc)); };
+  auto st_ok = [&](int l, int n) { return l < weff && (band != 1 || in_band(n, ky, nb, Nc)); };
   if constexpr (NS > 0) {
     // line l = column m0 + l; first pass straight from memory, last pass
     // straight to memory
     fft_direct<NS, WS, true, kEmax, false>(
         buf, W, W, 1, wsh, tw, sign, tid, nthr,
-        [&](int l, int n) { return l < weff ? base[(long)n * M + m0 + l] : make_float2(0.f, 0.f); },
+        [&](int l, int n) { return ld_ok(l, n) ? base[(long)n * M + m0 + l] : make_float2(0.f, 0.f); },
         [&] { fill_twiddles(tw, Nc, tid, nthr); },
         [&](int l, int n, float2 v) {
-          if (l < weff) base[(long)n * M + m0 + l] = v;
+          if (st_ok(l, n)) base[(long)n * M + m0 + l] = v;
         });
   } else {
     gather_to_lds(buf, Nc * W, tid, nthr, [&](int e) {
       const int n = e >> wsh, w = e & (W - 1);
-      return w < weff ? base[(long)n * M + m0 + w] : make_float2(0.f, 0.f);
+      return ld_ok(w, n) ? base[(long)n * M + m0 + w] : make_float2(0.f, 0.f);
     }, [&] { fill_twiddles(tw, Nc, tid, nthr); });
     __syncthreads();
     fft_lines<NS, WS, true>(buf, LdsLines{W, W, 1, true, wsh}, plan, tw, sign, tid, nthr);
     scatter_from_lds(buf, Nc * W, tid, nthr, [&](int e, float2 v) {
       const int n = e >> wsh, w = e & (W - 1);
-      if (w < weff) base[(long)n * M + m0 + w] = v;
+      if (st_ok(w, n)) base[(long)n * M + m0 + w] = v;
     });
   }
 }
@@ -327,11 +355,13 @@ static FftChoice cols_default(int N) {
 }
 
 hipError_t launch_cols(float2* data, int N, long M, long planes_per_group, long group_stride,
-                       long ngroups, float sign, hipStream_t s, const char* tag) {
-  const FftKey key{kFftCols, N, M, planes_per_group * ngroups, 0};
+                       long ngroups, float sign, hipStream_t s, const char* tag, int band, int ky) {
+  if (band < 0 || band > 2 || (band != 0 && ky < 0)) return hipErrorInvalidValue;
+  const int nb = band == 0 || 2L * ky + 1 >= N ? N : 2 * ky + 1;
+  const FftKey key{kFftCols, N, M, planes_per_group * ngroups, band};
   if (fft_recording())
     fft_record(key, [=] {
-      return launch_cols(data, N, M, planes_per_group, group_stride, ngroups, sign, s, tag);
+      return launch_cols(data, N, M, planes_per_group, group_stride, ngroups, sign, s, tag, band, ky);
     });
   FftChoice c;
   if (!fft_lookup(key, &c) || !cols_choice_ok(N, c)) c = cols_default(N);
@@ -347,10 +377,11 @@ hipError_t launch_cols(float2* data, int N, long M, long planes_per_group, long 
   case NN:                                                                                      \
     if (W == static_tile_width(NN))                                                             \
       hipLaunchKernelGGL((k_cols<NN, static_tile_width(NN)>), dim3((unsigned)nwg), dim3(thr), lds, \
-                         s, data, N, M, W, tiles, planes_per_group, group_stride, plan, sign);  \
+                         s, data, N, M, W, tiles, planes_per_group, group_stride, plan, sign, band, \
+                         ky, nb);                                                               \
     else                                                                                        \
       hipLaunchKernelGGL((k_cols<NN, 0>), dim3((unsigned)nwg), dim3(thr), lds, s, data, N, M, W, \
-                         tiles, planes_per_group, group_stride, plan, sign);                    \
+                         tiles, planes_per_group, group_stride, plan, sign, band, ky, nb);      \
     return hipGetLastError();
   if (c.plan == 0) switch (N) {
       WO_ALL_SIZES(X_)
@@ -359,7 +390,104 @@ hipError_t launch_cols(float2* data, int N, long M, long planes_per_group, long 
     }
 #undef X_
   hipLaunchKernelGGL((k_cols<0, 0>), dim3((unsigned)nwg), dim3(thr), lds, s, data, N, M, W, tiles,
-                     planes_per_group, group_stride, plan, sign);
+                     planes_per_group, group_stride, plan, sign, band, ky, nb);
+  return hipGetLastError();
+}
+
+// FFT along N of the columns kx < kt of the band rows, from compact planes
+// src [g][N][Y][kt] into full planes dst [g][N][Y][Xh].  Workgroup: W
+// consecutive columns of one band row of one plane group.  While its loads
+// are in flight a workgroup also writes the zeros of its share (zrows rows
+// from bid * zrows) of the rest of dst: rows outside the band, columns kx >= kt.
+template <int NS, int WS>
+__global__ __launch_bounds__(1024) void k_cols_expand(const float2* __restrict__ src,
+                                                      float2* __restrict__ dst, int N, int Y, int Xh,
+                                                      int kt, int ky, int nb, int Wrt,
+                                                      int tiles_row, long tiles_g, long zrows,
+                                                      long zrows_total, FftPlan plan, float sign) {
+  const int W = WS > 0 ? WS : Wrt;   // a power of two
+  const int wsh = WS > 0 ? pow2_shift(WS) : pow2_shift(Wrt);
+  extern __shared__ float2 smem[];
+  float2* tw = smem;
+  float2* buf = smem + N;
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const long bid = xcd_block();
+  const long g = bid / tiles_g;
+  const long t = bid - g * tiles_g;
+  const int b = (int)(t / tiles_row), j = (int)(t - (long)b * tiles_row);
+  const int y = band_row(b, ky, nb, Y);
+  const int kx0 = j * W;
+  const int weff = min(W, kt - kx0);
+  const long ms = (long)Y * kt, md = (long)Y * Xh;   // plane pitches
+  const float2* sb = src + g * N * ms + (long)y * kt + kx0;
+  float2* db = dst + g * N * md + (long)y * Xh + kx0;
+  const int Nc = NS > 0 ? NS : N;
+  auto mid = [&] {
+    fill_twiddles(tw, Nc, tid, nthr);
+    const long r0 = bid * zrows, r1 = min(r0 + zrows, zrows_total);
+    int yr = (int)(r0 % Y);
+    for (long row = r0; row < r1; ++row) {
+      float2* rp = dst + row * Xh;
+      for (int k = (in_band(yr, ky, nb, Y) ? kt : 0) + tid; k < Xh; k += nthr) rp[k] = make_float2(0.f, 0.f);
+      if (++yr == Y) yr = 0;
+    }
+  };
+  if constexpr (NS > 0) {
+    fft_direct<NS, WS, true, kEmax, false>(
+        buf, W, W, 1, wsh, tw, sign, tid, nthr,
+        [&](int l, int n) { return l < weff ? sb[(long)n * ms + l] : make_float2(0.f, 0.f); }, mid,
+        [&](int l, int n, float2 v) {
+          if (l < weff) db[(long)n * md + l] = v;
+        });
+  } else {
+    gather_to_lds(buf, Nc * W, tid, nthr, [&](int e) {
+      const int n = e >> wsh, w = e & (W - 1);
+      return w < weff ? sb[(long)n * ms + w] : make_float2(0.f, 0.f);
+    }, mid);
+    __syncthreads();
+    fft_lines<NS, WS, true>(buf, LdsLines{W, W, 1, true, wsh}, plan, tw, sign, tid, nthr);
+    scatter_from_lds(buf, Nc * W, tid, nthr, [&](int e, float2 v) {
+      const int n = e >> wsh, w = e & (W - 1);
+      if (w < weff) db[(long)n * md + w] = v;
+    });
+  }
+}
+
+hipError_t launch_cols_expand(const float2* src, float2* dst, int N, int Y, int Xh, int kt, int ky,
+                              long ngroups, float sign, hipStream_t s) {
+  if (kt < 1 || kt > Xh || ky < 0) return hipErrorInvalidValue;
+  const int nb = 2L * ky + 1 < Y ? 2 * ky + 1 : Y;
+  const int kyn = nb == Y ? Y : ky;
+  const FftChoice c = cols_default(N);
+  FftPlan plan;
+  if (!make_plan_variant(N, c.plan, &plan)) return hipErrorInvalidValue;
+  const int W = c.w;
+  const int tiles_row = (kt + W - 1) / W;
+  const long tiles_g = (long)nb * tiles_row;
+  const long nwg = tiles_g * ngroups;
+  const int thr = c.threads;
+  const size_t lds = (size_t)(N + N * W) * sizeof(float2);
+  const long zrows_total = ngroups * N * (long)Y;
+  const long zrows = (zrows_total + nwg - 1) / nwg;
+  ScopedTiming _t("k_cols_expand", s);
+#define X_(NN)                                                                                  \
+  case NN:                                                                                      \
+    if (W == static_tile_width(NN))                                                             \
+      hipLaunchKernelGGL((k_cols_expand<NN, static_tile_width(NN)>), dim3((unsigned)nwg), dim3(thr), \
+                         lds, s, src, dst, N, Y, Xh, kt, kyn, nb, W, tiles_row, tiles_g, zrows,  \
+                         zrows_total, plan, sign);                                              \
+    else                                                                                        \
+      hipLaunchKernelGGL((k_cols_expand<NN, 0>), dim3((unsigned)nwg), dim3(thr), lds, s, src, dst, N, \
+                         Y, Xh, kt, kyn, nb, W, tiles_row, tiles_g, zrows, zrows_total, plan, sign); \
+    return hipGetLastError();
+  if (c.plan == 0) switch (N) {
+      WO_AXIAL_SIZES(X_)
+      default:
+        break;
+    }
+#undef X_
+  hipLaunchKernelGGL((k_cols_expand<0, 0>), dim3((unsigned)nwg), dim3(thr), lds, s, src, dst, N, Y, Xh,
+                     kt, kyn, nb, W, tiles_row, tiles_g, zrows, zrows_total, plan, sign);
   return hipGetLastError();
 }
 
@@ -473,9 +601,19 @@ __device__ __forceinline__ void freq_op(float2* cell, long cs, HF H, int Crt, in
 
 constexpr int kTfPrefetch = 8;   // transfer-function values a thread may hold in registers
 
+// Geometry of the fused Z pass.  A plane of the spectrum holds R rows of row
+// pitch Ls (plane pitch Ms), a plane of the bank R rows of pitch Lt (plane
+// pitch Mt); the pass covers the columns k < kt of the band rows (band_row:
+// ky, nb) in tiles of W columns that do not cross a row.  The plain layout is
+// one row: R = 1, Ls = Lt = kt = Ms = Mt = M, nb = 1.
+struct ZopGeom {
+  long Ms, Mt, Ls, Lt, kt;
+  int R, ky, nb, tiles_row;
+};
+
 template <int P, int CT, int NS>
 __global__ __launch_bounds__(1024) void k_zop(float2* __restrict__ spec,
-                                              const float2* __restrict__ tf, int C, int Z, long M,
+                                              const float2* __restrict__ tf, int C, int Z, ZopGeom gm,
                                               int slots, int W, long tiles_m, FftPlan plan,
                                               int mode, float eta, const float* __restrict__ bg,
                                               float inv_n, float n_full) {
@@ -491,12 +629,18 @@ __global__ __launch_bounds__(1024) void k_zop(float2* __restrict__ spec,
   const int cin = mode == kModeForward ? P : C;
   const int cout = mode == kModeForward ? C : P;
   const int CH = cin > cout ? cin : cout;
-  float2* sp = spec + patch * (long)slots * Z * M;
-  const float2* tp = tf + patch * (long)C * P * Z * M;
+  const long Ms = gm.Ms, Mt = gm.Mt;
+  float2* sp = spec + patch * (long)slots * Z * Ms;
+  const float2* tp = tf + patch * (long)C * P * Z * Mt;
   const float* bp = bg ? bg + patch * C : nullptr;
-  const long m0 = tile * W;
-  const int weff = (int)min((long)W, M - m0);
-  const long ts = (long)Z * M;               // stride between (c, p) entries of the bank
+  const int brow = (int)(tile / gm.tiles_row);
+  const long col0 = (tile - (long)brow * gm.tiles_row) * W;
+  const int row = band_row(brow, gm.ky, gm.nb, gm.R);
+  const long m0 = row * gm.Ls + col0;        // tile start in a spectrum plane
+  const long mt0 = row * gm.Lt + col0;       // and in a bank plane
+  const bool dc_tile = row == 0 && col0 == 0;
+  const int weff = (int)min((long)W, gm.kt - col0);
+  const long ts = (long)Z * Mt;              // stride between (c, p) entries of the bank
   // Issue this thread's transfer-function loads first: they complete while the
   // data tile is loaded and transformed.  Frequency f = tid + i * nthr.
   const int nfreq = Zc * W;
@@ -510,7 +654,7 @@ __global__ __launch_bounds__(1024) void k_zop(float2* __restrict__ spec,
       const int f = tid + i * nthr;
       if (i < fpt && f < nfreq) {
         const int z = f >> wsh, w = f & (W - 1);
-        hreg[j] = w < weff ? tp[cp * ts + (long)z * M + m0 + w] : make_float2(0.f, 0.f);
+        hreg[j] = w < weff ? tp[cp * ts + (long)z * Mt + mt0 + w] : make_float2(0.f, 0.f);
       }
     }
   }
@@ -521,7 +665,7 @@ __global__ __launch_bounds__(1024) void k_zop(float2* __restrict__ spec,
         buf, cin * W, CH * W, 1, pow2_shift(cin * W), -1.f, tid, nthr,
         [&](int l, int z) {
           const int ch = l >> wsh, w = l & (W - 1);
-          return w < weff ? sp[((long)ch * Z + z) * M + m0 + w] : make_float2(0.f, 0.f);
+          return w < weff ? sp[((long)ch * Z + z) * Ms + m0 + w] : make_float2(0.f, 0.f);
         },
         [&] { fill_twiddles(tw, Z, tid, nthr); });
     static_passes<NS, 0, true, kEmax, false, false, 1, StaticPlan<NS>::passes()>(
@@ -535,7 +679,7 @@ __global__ __launch_bounds__(1024) void k_zop(float2* __restrict__ spec,
       if (e < cin * Zc * W) {
         const int w = e & (W - 1), r = e >> wsh;
         const int z = r % Zc, ch = r / Zc;
-        t[i] = w < weff ? sp[((long)ch * Z + z) * M + m0 + w] : make_float2(0.f, 0.f);
+        t[i] = w < weff ? sp[((long)ch * Z + z) * Ms + m0 + w] : make_float2(0.f, 0.f);
       }
     }
     fill_twiddles(tw, Z, tid, nthr);
@@ -559,10 +703,9 @@ __global__ __launch_bounds__(1024) void k_zop(float2* __restrict__ spec,
       if (i < fpt && f < nfreq) {
         const int z = f >> wsh, w = f & (W - 1);
         if (w < weff) {
-          const long m = m0 + w;
           freq_op<P, 1>(buf + (long)z * CH * W + w, W,
                         [&](int c, int p) { return hreg[i * P + p]; }, C, mode, eta, bp,
-                        z == 0 && m == 0, n_full, inv_n);
+                        z == 0 && dc_tile && w == 0, n_full, inv_n);
         }
       }
     }
@@ -570,11 +713,10 @@ __global__ __launch_bounds__(1024) void k_zop(float2* __restrict__ spec,
     for (int f = tid; f < nfreq; f += nthr) {
       const int z = f >> wsh, w = f & (W - 1);
       if (w >= weff) continue;
-      const long m = m0 + w;
-      const float2* hp = tp + (long)z * M + m;
+      const float2* hp = tp + (long)z * Mt + mt0 + w;
       freq_op<P, CT>(buf + (long)z * CH * W + w, W,
                      [&](int c, int p) { return hp[(long)(c * P + p) * ts]; }, C, mode, eta, bp,
-                     z == 0 && m == 0, n_full, inv_n);
+                     z == 0 && dc_tile && w == 0, n_full, inv_n);
     }
   }
   __syncthreads();
@@ -586,7 +728,7 @@ __global__ __launch_bounds__(1024) void k_zop(float2* __restrict__ spec,
         buf, cout * W, CH * W, 1, pow2_shift(cout * W), tw, 1.f, tid, nthr,
         [&](int l, int z, float2 v) {
           const int ch = l >> wsh, w = l & (W - 1);
-          if (w < weff) sp[((long)ch * Z + z) * M + m0 + w] = v;
+          if (w < weff) sp[((long)ch * Z + z) * Ms + m0 + w] = v;
         });
   } else {
     fft_lines<NS, 0, true>(buf, LdsLines{cout * W, CH * W, 1, true, pow2_shift(cout * W)}, plan, tw, 1.f,
@@ -607,7 +749,7 @@ __global__ __launch_bounds__(1024) void k_zop(float2* __restrict__ spec,
       if (e < cout * Zc * W) {
         const int w = e & (W - 1), r = e >> wsh;
         const int z = r % Zc, ch = r / Zc;
-        if (w < weff) sp[((long)ch * Z + z) * M + m0 + w] = t[i];
+        if (w < weff) sp[((long)ch * Z + z) * Ms + m0 + w] = t[i];
       }
     }
   }
@@ -615,11 +757,11 @@ __global__ __launch_bounds__(1024) void k_zop(float2* __restrict__ spec,
 
 template <int P, int CT>
 static void zop_launch(bool use_static, long nwg, int thr, size_t lds, hipStream_t s, float2* spec,
-                       const float2* tf, int C, int Z, long M, int slots, int W, long tiles,
+                       const float2* tf, int C, int Z, const ZopGeom& gm, int slots, int W, long tiles,
                        FftPlan plan, int mode, float eta, const float* bg, float inv_n, float nf) {
 #define X_(NN)                                                                                   \
   case NN:                                                                                       \
-    hipLaunchKernelGGL((k_zop<P, CT, NN>), dim3((unsigned)nwg), dim3(thr), lds, s, spec, tf, C, Z, M, \
+    hipLaunchKernelGGL((k_zop<P, CT, NN>), dim3((unsigned)nwg), dim3(thr), lds, s, spec, tf, C, Z, gm, \
                        slots, W, tiles, plan, mode, eta, bg, inv_n, nf);                         \
     return;
   if (use_static) switch (Z) {
@@ -628,7 +770,7 @@ static void zop_launch(bool use_static, long nwg, int thr, size_t lds, hipStream
         break;
     }
 #undef X_
-  hipLaunchKernelGGL((k_zop<P, CT, 0>), dim3((unsigned)nwg), dim3(thr), lds, s, spec, tf, C, Z, M,
+  hipLaunchKernelGGL((k_zop<P, CT, 0>), dim3((unsigned)nwg), dim3(thr), lds, s, spec, tf, C, Z, gm,
                      slots, W, tiles, plan, mode, eta, bg, inv_n, nf);
 }
 
@@ -647,11 +789,19 @@ bool zop_fits(int Z, int CH) { return zop_choice_ok(Z, CH, zop_default(Z, CH)); 
 
 hipError_t launch_zop(float2* spec, const float2* tf, int C, int P, int Z, long M, int slots,
                       int npatch, int mode, float eta, const float* bg, float inv_n, double n_full,
-                      hipStream_t s) {
-  const FftKey key{kFftZop, Z, M, npatch, P * 1000 + C * 10 + mode};
+                      hipStream_t s, const SpecBand* band) {
+  if (band && (band->Y < 1 || M % band->Y != 0 || band->kt < 1 || band->kt > M / band->Y ||
+               band->ky < 0))
+    return hipErrorInvalidValue;
+  const bool hb = band != nullptr;
+  const SpecBand bc = hb ? *band : SpecBand{1, M, 0};
+  const int nbr = hb ? (2L * bc.ky + 1 >= bc.Y ? bc.Y : 2 * bc.ky + 1) : 1;
+  const long mcov = hb ? (long)nbr * bc.kt : M;   // columns the pass covers per plane
+  const FftKey key{kFftZop, Z, mcov, npatch, P * 1000 + C * 10 + mode + (hb ? 100000 : 0)};
   if (fft_recording())
     fft_record(key, [=] {
-      return launch_zop(spec, tf, C, P, Z, M, slots, npatch, mode, eta, bg, inv_n, n_full, s);
+      return launch_zop(spec, tf, C, P, Z, M, slots, npatch, mode, eta, bg, inv_n, n_full, s,
+                        hb ? &bc : nullptr);
     });
   const int cin = mode == kModeForward ? P : C;
   const int cout = mode == kModeForward ? C : P;
@@ -661,7 +811,17 @@ hipError_t launch_zop(float2* spec, const float2* tf, int C, int P, int Z, long 
   FftPlan plan;
   if (!make_plan_variant(Z, c.plan, &plan)) return hipErrorInvalidValue;
   const int W = c.w;
-  const long tiles = (M + W - 1) / W;
+  ZopGeom gm;
+  gm.R = bc.Y;
+  gm.kt = bc.kt;
+  gm.Ls = bc.kt;
+  gm.Lt = M / bc.Y;
+  gm.Ms = (long)bc.Y * bc.kt;
+  gm.Mt = M;
+  gm.nb = nbr;
+  gm.ky = nbr == bc.Y ? bc.Y : bc.ky;
+  gm.tiles_row = (int)((bc.kt + W - 1) / W);
+  const long tiles = (long)nbr * gm.tiles_row;
   const long nwg = tiles * npatch;
   const int thr = c.threads;
   const size_t lds = (size_t)(Z + CH * Z * W) * sizeof(float2);
@@ -669,7 +829,7 @@ hipError_t launch_zop(float2* spec, const float2* tf, int C, int P, int Z, long 
   const bool st = c.plan == 0;
   ScopedTiming _t(P == 1 ? "k_zop<1>" : (P == 2 ? "k_zop<2>" : "k_zop<4>"), s);
 #define WO_ZOP(PP, CC) \
-  zop_launch<PP, CC>(st, nwg, thr, lds, s, spec, tf, C, Z, M, slots, W, tiles, plan, mode, eta, bg, inv_n, nf)
+  zop_launch<PP, CC>(st, nwg, thr, lds, s, spec, tf, C, Z, gm, slots, W, tiles, plan, mode, eta, bg, inv_n, nf)
   if (P == 1) { if (C == 1) WO_ZOP(1, 1); else WO_ZOP(1, 0); }
   else if (P == 2) { if (C == 1) WO_ZOP(2, 1); else WO_ZOP(2, 0); }
   else if (P == 4) { if (C == 1) WO_ZOP(4, 1); else WO_ZOP(4, 0); }
@@ -751,7 +911,7 @@ std::vector<FftChoice> fft_candidates(const FftKey& k) {
           if (tf_rows_choice_ok(k.n, c)) add(c);
         }
   } else if (k.kind == kFftZop) {
-    const int P = k.extra / 1000, C = (k.extra / 10) % 100, mode = k.extra % 10;
+    const int P = (k.extra % 100000) / 1000, C = (k.extra / 10) % 100, mode = k.extra % 10;
     const int cin = mode == kModeForward ? P : C;
     const int cout = mode == kModeForward ? C : P;
     const int CH = cin > cout ? cin : cout;

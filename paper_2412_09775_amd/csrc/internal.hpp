@@ -99,25 +99,46 @@ struct RowGroups {
   long ngroups;
 };
 
-// Real rows -> half-spectrum rows (forward, unnormalised).
-hipError_t launch_rows_r2c(const float* in, float2* out, int X, const RowGroups& g, hipStream_t s);
-// Half-spectrum rows -> real rows times `scale` (inverse).
+// Real rows -> half-spectrum rows (forward, unnormalised): the columns k < kt
+// (0: all X/2 + 1) of each output row, row pitch `pitch` (0: X/2 + 1).
+hipError_t launch_rows_r2c(const float* in, float2* out, int X, const RowGroups& g, hipStream_t s,
+                           int kt = 0, int pitch = 0);
+// Half-spectrum rows -> real rows times `scale` (inverse); input rows of
+// pitch `pitch` hold the columns k < kt, the others are taken as zero.
 hipError_t launch_rows_c2r(const float2* in, float* out, int X, const RowGroups& g, float scale,
-                           hipStream_t s);
+                           hipStream_t s, int kt = 0, int pitch = 0);
 // In-place FFT along the middle axis of planes [N][M]; plane p of group g
 // starts at data + (g * group_stride + p) * N * M.
+// band: 0 every row; 1 stores only the band rows n <= ky or n >= N - ky of
+// the transform; 2 loads only those (the others are taken as zero).
 hipError_t launch_cols(float2* data, int N, long M, long planes_per_group, long group_stride,
-                       long ngroups, float sign, hipStream_t s, const char* tag = "k_cols");
+                       long ngroups, float sign, hipStream_t s, const char* tag = "k_cols",
+                       int band = 0, int ky = -1);
+// FFT along N of the band rows of compact planes src [g][N][Y][kt] into the
+// full half-spectrum planes dst [g][N][Y][Xh]; every other value of dst (rows
+// outside the band, columns kx >= kt) is set to zero.
+hipError_t launch_cols_expand(const float2* src, float2* dst, int N, int Y, int Xh, int kt, int ky,
+                              long ngroups, float sign, hipStream_t s);
 
 enum SpectralMode { kModeForward = 0, kModeSolve = 1, kModeAdjoint = 2 };
 
 // Whether one Z line of CH channels fits a workgroup of the fused Z pass.
 bool zop_fits(int Z, int CH);
+// Lateral band of a compact spectrum: planes of Y rows holding the
+// half-spectrum columns k < kt; the band rows are y <= ky and y >= Y - ky.
+struct SpecBand {
+  int Y;
+  long kt;
+  int ky;
+};
 // 3D: forward Z-FFT, per-frequency op, inverse Z-FFT, fused.  spec holds
 // `slots` channel slots of [Z][M] per patch; tf holds [C][P][Z][M] per patch.
+// With a band, spec holds `slots` slots of [Z][Y][kt] instead (M = Y * Xh
+// stays the bank's plane) and only the band rows' columns k < kt are
+// transformed; the rest of spec is left as it is.
 hipError_t launch_zop(float2* spec, const float2* tf, int C, int P, int Z, long M, int slots,
                       int npatch, int mode, float eta, const float* bg, float inv_n, double n_full,
-                      hipStream_t s);
+                      hipStream_t s, const SpecBand* band = nullptr);
 // 2D (thin) per-frequency op: spec [slots][M] per patch, tf [C][P][M] per patch.
 // eta_pp (device [npatch], may be NULL) overrides eta per patch.
 hipError_t launch_op2d(float2* spec, const float2* tf, int C, int P, long M, int slots, int npatch,
@@ -126,16 +147,33 @@ hipError_t launch_op2d(float2* spec, const float2* tf, int C, int P, long M, int
 
 // Transfer-function synthesis.
 hipError_t launch_set_params(DevOptics* dst, const DevOptics* host, int n, hipStream_t s);
+// Lateral support of the label-free fields and transfer function.  The field
+// kernel stores xc compact columns of its fields (field_column, last
+// non-negative column kp); the label-free row kernel writes the transfer
+// function's half-spectrum columns kx < kt; the band Z pass transforms rows
+// y <= ky or y >= Y - ky (ky = Y: every row).  full_support is the plain
+// layout.
+struct LatSupport {
+  int xc, kp;
+  int kt;
+  int ky;
+};
+inline LatSupport full_support(const Sampling& sm) {
+  return LatSupport{sm.nx, sm.nx - 1, sm.nx / 2 + 1, sm.ny};
+}
 // Column tile width of the field kernel; the pupil-sum partials hold
-// ceil(nx / width) doubles per patch.
+// ceil(xc / width) doubles per patch.
 int tf_tile_width(const Sampling& sm);
 // Planes per workgroup of the z-chunked field and gradient kernels.
 int tf_z_chunk(const Sampling& sm, long tiles_x, long npatch, long target);
 hipError_t launch_tf_fields_y(const DevOptics* opt, const Sampling& sm, int npatch, float2* ab,
-                              double* partials, hipStream_t s);
+                              double* partials, hipStream_t s, const LatSupport* sup = nullptr);
+// out[patch * patch_stride + p * pstride + z * zstride + y * pitch + k], k < sup->kt
+// (pitch: Xh, or sup->kt when the caller keeps the compact columns).
 hipError_t launch_tf_rows_labelfree(const double* partials, const Sampling& sm, int npatch,
                                     const float2* ab, float2* out, long patch_stride,
-                                    long pstride, long zstride, hipStream_t s);
+                                    long pstride, long zstride, hipStream_t s,
+                                    const LatSupport* sup = nullptr, int pitch = 0);
 hipError_t launch_tf_rows_fluor(const double* partials, const Sampling& sm, int npatch,
                                 const float2* h, float2* out, hipStream_t s);
 hipError_t launch_tf_pol5_z(const DevOptics* opt, const Sampling& sm, int npatch, float2* uw,

@@ -79,8 +79,9 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
 
 // ------------------------------------------------------------------ fields, inverse Y
 
-// ab layout: [patch][field][z][y][x] complex (field 0 = A or the fluorescence
-// field, field 1 = B).  A workgroup owns one column tile of one patch and a
+// ab layout: [patch][field][z][y][c] complex (field 0 = A or the fluorescence
+// field, field 1 = B), c the compact column of the lateral frequency kx (see
+// field_column; c = kx when XC = X).  A workgroup owns one column tile of one patch and a
 // chunk of ZC consecutive planes: the pupil values, which do not depend on z,
 // are evaluated once into registers; each plane then only needs its phase.
 // The workgroup of the first chunk also writes the tile's share of the pupil
@@ -90,7 +91,8 @@ template <int NS, int NF, bool AB>
 __global__ __launch_bounds__(1024) void k_tf_fields_y(const DevOptics* __restrict__ opt,
                                                       Sampling sm, float2* __restrict__ ab,
                                                       double* __restrict__ partials, int W,
-                                                      long tiles_x, int ZC, FftPlan plan) {
+                                                      long tiles_x, int ZC, int XC, int KP,
+                                                      FftPlan plan) {
   __shared__ double red[kMaxThreads / 64];
   extern __shared__ float2 smem[];
   const int Y = sm.ny, X = sm.nx, Z = sm.nz;
@@ -137,13 +139,14 @@ __global__ __launch_bounds__(1024) void k_tf_fields_y(const DevOptics* __restric
       for (int b = 0; b < B0; ++b) {
         const int j = tid + b * nthr;
         const int l = j & (nl - 1), k = j >> lsh;
-        const int f = l >> wsh, kx = x0 + (l & (W - 1));
+        const int f = l >> wsh, c = x0 + (l & (W - 1));
+        const int kx = field_column(c, KP, X, XC);
 #pragma unroll
         for (int r = 0; r < R0; ++r) {
           tkz[b][r] = 0.0;
           fac[b][r] = 0.f;
           if constexpr (AB) ab2[b][r] = 0.f;
-          if (j < nl * NB0 && kx < X) {
+          if (j < nl * NB0 && c < XC) {
             const int ky = k + r * NB0;
             const double fy = fftfreq(ky, Y, sm.dy), fx = fftfreq(kx, X, sm.dx);
             const double P = disc(fy, fx, rd, hw);
@@ -221,11 +224,11 @@ __global__ __launch_bounds__(1024) void k_tf_fields_y(const DevOptics* __restric
             if (r > 0) v[r] = cmul(v[r], w[r]);
           }
           dft_small<RL>(v, 1.f);
-          const int f = l >> wsh, kx = x0 + (l & (W - 1));
-          if (kx < X) {
-            float2* dst = ab + ((patch * nf + f) * Z + z) * (long)Y * X + kx;
+          const int f = l >> wsh, c = x0 + (l & (W - 1));
+          if (c < XC) {
+            float2* dst = ab + ((patch * nf + f) * Z + z) * (long)Y * XC + c;
 #pragma unroll
-            for (int r = 0; r < RL; ++r) dst[(long)(k + r * NSL) * X] = v[r];
+            for (int r = 0; r < RL; ++r) dst[(long)(k + r * NSL) * XC] = v[r];
           }
         }
       }
@@ -251,8 +254,9 @@ __global__ __launch_bounds__(1024) void k_tf_fields_y(const DevOptics* __restric
         const int e = tid + i * nthr;
         if (e < Y * W) {
           const int ky = e >> wsh, w = e & (W - 1);
-          const int kx = x0 + w;
-          if (kx < X) {
+          const int c = x0 + w;
+          const int kx = field_column(c, KP, X, XC);
+          if (c < XC) {
             const double fy = fftfreq(ky, Y, sm.dy), fx = fftfreq(kx, X, sm.dx);
             const double P = disc(fy, fx, rd, hw);
             if (P != 0.0) {
@@ -310,8 +314,8 @@ __global__ __launch_bounds__(1024) void k_tf_fields_y(const DevOptics* __restric
         const int ky = e >> (wsh + nf - 1);
         const int r = e & (nf * W - 1);
         const int f = r >> wsh, w = r & (W - 1);
-        const int kx = x0 + w;
-        if (kx < X) ab[(((patch * nf + f) * Z + z) * (long)Y + ky) * X + kx] = v;
+        const int c = x0 + w;
+        if (c < XC) ab[(((patch * nf + f) * Z + z) * (long)Y + ky) * XC + c] = v;
       });
       __syncthreads();
     }
@@ -343,12 +347,14 @@ int tf_tile_width(const Sampling& sm) {
 }
 
 hipError_t launch_tf_fields_y(const DevOptics* opt, const Sampling& sm, int npatch, float2* ab,
-                              double* partials, hipStream_t s) {
+                              double* partials, hipStream_t s, const LatSupport* sup) {
   FftPlan plan;
   if (!make_plan(sm.ny, &plan)) return hipErrorInvalidValue;
+  const LatSupport ls = sup ? *sup : full_support(sm);
+  if (ls.xc < 1 || ls.xc > sm.nx || ls.kp < 0 || ls.kp >= ls.xc) return hipErrorInvalidValue;
   const int nf = sm.model == kFluor3D ? 1 : 2;
   const int W = tf_tile_width(sm);
-  const long tiles = (sm.nx + W - 1) / W;
+  const long tiles = (ls.xc + W - 1) / W;
   const int ZC = tf_z_chunk(sm, tiles, npatch, 2048);
   const long nwg = tiles * ((sm.nz + ZC - 1) / ZC) * (long)npatch;
   const int thr = threads_for((long)sm.ny * nf * W);
@@ -356,7 +362,7 @@ hipError_t launch_tf_fields_y(const DevOptics* opt, const Sampling& sm, int npat
   ScopedTiming _t("k_tf_fields_y", s);
 #define WO_FIELDS(NN, FF, AA)                                                                    \
   hipLaunchKernelGGL((k_tf_fields_y<NN, FF, AA>), dim3((unsigned)nwg), dim3(thr), lds, s, opt, sm, ab, \
-                     partials, W, tiles, ZC, plan)
+                     partials, W, tiles, ZC, ls.xc, ls.kp, plan)
 #define X_(NN)                                                                                   \
   case NN:                                                                                       \
     if (nf == 2) {                                                                               \
@@ -382,8 +388,10 @@ hipError_t launch_tf_fields_y(const DevOptics* opt, const Sampling& sm, int npat
 
 // ------------------------------------------------------------------ rows: label-free
 
-// out[patch * patch_stride + p * pstride + z * zstride + y * Xh + k], p = 0 phase, 1 absorption
-// (pstride < 0: phase only)
+// out[patch * patch_stride + p * pstride + z * zstride + y * OP + k], k < KT,
+// p = 0 phase, 1 absorption (pstride < 0: phase only).  The fields are read in
+// the compact column layout of the field kernel (XC columns, last
+// non-negative column KP); the columns it does not store are zero.
 
 template <int NS>
 __global__ __launch_bounds__(1024) void k_tf_rows_lf(const double* __restrict__ partials,
@@ -391,12 +399,12 @@ __global__ __launch_bounds__(1024) void k_tf_rows_lf(const double* __restrict__ 
                                                      const float2* __restrict__ ab,
                                                      float2* __restrict__ out, long patch_stride,
                                                      long pstride, long zstride, int rows_per_wg,
-                                                     long wg_per_patch, FftPlan plan) {
+                                                     long wg_per_patch, int XC, int KP, int KT,
+                                                     int OP, FftPlan plan) {
   __shared__ double ibg_s;
   extern __shared__ float2 smem[];
   const int Y = sm.ny, Z = sm.nz;
   const int X = NS > 0 ? NS : sm.nx;   // compile-time length for the index arithmetic
-  const int Xh = X / 2 + 1;
   float2* tw = smem;
   float2* buf = smem + X;
   const int tid = threadIdx.x, nthr = blockDim.x;
@@ -406,12 +414,17 @@ __global__ __launch_bounds__(1024) void k_tf_rows_lf(const double* __restrict__ 
   const long row0 = (blockIdx.x - patch * wg_per_patch) * (long)rows_per_wg;
   const int nr = (int)min((long)rows_per_wg, rpp - row0);
   const int z0 = (int)(row0 / Y), y0 = (int)(row0 - (long)z0 * Y);
-  const float2* a_src = ab + (patch * 2 + 0) * rpp * X;
-  const float2* b_src = ab + (patch * 2 + 1) * rpp * X;
+  const float2* a_src = ab + (patch * 2 + 0) * rpp * XC;
+  const float2* b_src = ab + (patch * 2 + 1) * rpp * XC;
   const int PS = pad_shift(X);   // row padding
   const int LS = row_stride(X);      // padded line pitch in LDS
-  // line 2r holds a, line 2r + 1 holds b of row r
-  auto load = [&](int t, int i) { return ((t & 1) ? b_src : a_src)[(row0 + (t >> 1)) * X + i]; };
+  const int neg0 = X - (XC - KP - 1);   // first stored negative-frequency column
+  // line 2r holds a, line 2r + 1 holds b of row r; the condition depends on
+  // the index only, so the loads of a thread stay in flight together
+  auto load = [&](int t, int i) {
+    const float2* src = ((t & 1) ? b_src : a_src) + (row0 + (t >> 1)) * XC;
+    return (i <= KP || i >= neg0) ? src[i <= KP ? i : i - (X - XC)] : make_float2(0.f, 0.f);
+  };
   if constexpr (NS > 0) {
     // Inverse transforms of a and b in reversed radix order, the first pass
     // straight from memory; their last pass, the product c = b conj(a) /
@@ -496,16 +509,17 @@ __global__ __launch_bounds__(1024) void k_tf_rows_lf(const double* __restrict__ 
                                          tid, nthr);
   }
   float2* op = out + patch * patch_stride;
-  for (int e = tid; e < nr * Xh; e += nthr) {
-    const int r = e / Xh, k = e - r * Xh;
+  const float inv_kt = 1.0f / (float)KT;
+  for (int e = tid; e < nr * KT; e += nthr) {
+    const int r = div_small(e, inv_kt), k = e - r * KT;
     const float2 Ck = buf[2 * r * LS + row_slot(k, PS)];
     const float2 Cm = buf[2 * r * LS + row_slot(k == 0 ? 0 : X - k, PS)];
     int y = y0 + r, z = z0;
     while (y >= Y) { y -= Y; ++z; }
     const float2 U = make_float2(Ck.x + Cm.x, Ck.y - Cm.y);          // C + conj(C(-k))
     const float2 V = make_float2(-(Ck.y + Cm.y), Ck.x - Cm.x);       // i (C - conj(C(-k)))
-    op[(long)z * zstride + (long)y * Xh + k] = U;
-    if (pstride >= 0) op[pstride + (long)z * zstride + (long)y * Xh + k] = V;
+    op[(long)z * zstride + (long)y * OP + k] = U;
+    if (pstride >= 0) op[pstride + (long)z * zstride + (long)y * OP + k] = V;
   }
 }
 
@@ -527,15 +541,23 @@ FftChoice tf_rows_default(int X) {
 
 hipError_t launch_tf_rows_labelfree(const double* partials, const Sampling& sm, int npatch,
                                     const float2* ab, float2* out, long patch_stride,
-                                    long pstride, long zstride, hipStream_t s) {
+                                    long pstride, long zstride, hipStream_t s,
+                                    const LatSupport* sup, int pitch) {
+  const LatSupport ls = sup ? *sup : full_support(sm);
+  const int Xh = sm.nx / 2 + 1;
+  if (ls.xc < 1 || ls.xc > sm.nx || ls.kp < 0 || ls.kp >= ls.xc || ls.kt < 1 || ls.kt > Xh)
+    return hipErrorInvalidValue;
+  const int OP = pitch > 0 ? pitch : Xh;
+  if (OP < ls.kt) return hipErrorInvalidValue;
   const FftKey key{kFftTfRows, sm.nx, sm.ny, (long)npatch * sm.nz, pstride < 0 ? 1 : 0};
   if (fft_recording())
     fft_record(key, [=] {
-      return launch_tf_rows_labelfree(partials, sm, npatch, ab, out, patch_stride, pstride, zstride, s);
+      return launch_tf_rows_labelfree(partials, sm, npatch, ab, out, patch_stride, pstride, zstride, s,
+                                      &ls, OP);
     });
   FftChoice c;
   if (!fft_lookup(key, &c) || !tf_rows_choice_ok(sm.nx, c)) c = tf_rows_default(sm.nx);
-  const long tiles_x = (sm.nx + tf_tile_width(sm) - 1) / tf_tile_width(sm);
+  const long tiles_x = (ls.xc + tf_tile_width(sm) - 1) / tf_tile_width(sm);
   FftPlan plan;
   if (!make_plan_variant(sm.nx, c.plan, &plan)) return hipErrorInvalidValue;
   const int R = c.w;
@@ -548,7 +570,8 @@ hipError_t launch_tf_rows_labelfree(const double* partials, const Sampling& sm, 
 #define X_(NN)                                                                                   \
   case NN:                                                                                       \
     hipLaunchKernelGGL((k_tf_rows_lf<NN>), dim3((unsigned)nwg), dim3(thr), lds, s, partials, tiles_x, \
-                       sm, ab, out, patch_stride, pstride, zstride, R, wpp, plan);               \
+                       sm, ab, out, patch_stride, pstride, zstride, R, wpp, ls.xc, ls.kp, ls.kt, OP, \
+                       plan);                                                                    \
     return hipGetLastError();
   if (c.plan == 0) switch (sm.nx) {
       WO_LATERAL_SIZES(X_)
@@ -557,7 +580,7 @@ hipError_t launch_tf_rows_labelfree(const double* partials, const Sampling& sm, 
     }
 #undef X_
   hipLaunchKernelGGL((k_tf_rows_lf<0>), dim3((unsigned)nwg), dim3(thr), lds, s, partials, tiles_x, sm,
-                     ab, out, patch_stride, pstride, zstride, R, wpp, plan);
+                     ab, out, patch_stride, pstride, zstride, R, wpp, ls.xc, ls.kp, ls.kt, OP, plan);
   return hipGetLastError();
 }
 

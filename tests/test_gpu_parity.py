@@ -98,6 +98,15 @@ CASES = {
     "thin_aberrated_batch2": [thin(zernike=(0.1,)), thin(zernike=(0.0,) * 6 + (0.2,), defocus=0.5)],
     "pol5_aberrated": [pol5(zernike=(0.0, 0.0, 0.1))],
     "sectors9_aberrated": [sectors(zernike=(0.05, 0.05, 0.1))],
+    # lateral band limits well inside the grid: the fields are kept on the
+    # detection pupil's columns and the transfer function on its support until
+    # the Z pass; a batch of two with different pupils (the support is their union)
+    "labelfree_3d_band_batch2": [labelfree(nz=16, ny=96, nx=128, defocus=0.3, tilt_zenith=0.35,
+                                           tilt_azimuth=2.0, edge_width=0.5),
+                                 labelfree(nz=16, ny=96, nx=128, na_det=1.0, na_ill=0.3,
+                                           edge_width=0.25)],
+    "sectors9_band": [sectors(nz=12, ny=96, nx=128, tilt_zenith=0.2, tilt_azimuth=-0.7,
+                              edge_width=0.5)],
 }
 
 
@@ -221,6 +230,20 @@ def test_adjoint_matches_oracle(gpu_lib, torch, name):
         err = rel_l2(got[i], ref)
         print(f"  patch {i}: rel L2 = {err:.3e}")
         assert err < TOL_ADJ
+
+
+@pytest.mark.parametrize("name", ["labelfree_3d_band_batch2", "sectors9_band", "labelfree_3d_tilt_soft"])
+def test_transfer_function_elementwise_at_support_edge(gpu_lib, torch, name):
+    """Every value, including the faint ring at the edge of the support, within
+    1e-5 of the largest (a support bound one column short fails this)."""
+    opts = CASES[name]
+    print(f"[case] tf elementwise {name}", flush=True)
+    got = gpu_lib.transfer_function(opts).cpu().numpy()
+    for i, o in enumerate(opts):
+        ref = half(oracle_bank(o))
+        err = np.max(np.abs(got[i] - ref)) / np.max(np.abs(ref))
+        print(f"  patch {i}: max abs err / max = {err:.3e}")
+        assert err < 1e-5
 
 
 def test_fluorescence_eta_zero_is_pseudo_inverse(gpu_lib, torch):

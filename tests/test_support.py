@@ -1,0 +1,79 @@
+"""The lateral support the library reports (and prunes to) contains the support
+of the oracle's fields and transfer-function bank, and is tight (CPU only: the
+query is host logic).
+
+The fields are zero outside the detection pupil's columns, and the bank outside
+the sum of the detection and illumination supports (twice the detection
+pupil's for fluorescence); the bounds keep one spare column or row and round up
+to multiples of 16."""
+
+import numpy as np
+import pytest
+
+from oracle import optics as op
+from oracle import tf as tfm
+from paper_2412_09775_amd import api
+
+
+def lf(**kw):
+    o = op.Optics(model=op.LABELFREE_3D, nz=8, ny=96, nx=128, dz=0.2, dy=0.1, dx=0.1,
+                  wavelength=0.532, na_ill=0.5, na_det=1.2, n_medium=1.33)
+    return o.replace(**kw)
+
+
+CASES = {
+    "labelfree": [lf()],
+    "labelfree_tilt_soft": [lf(tilt_zenith=0.35, tilt_azimuth=2.0, edge_width=0.5, defocus=0.3)],
+    "labelfree_batch_union": [lf(na_det=1.0, na_ill=0.3), lf(na_det=1.25, tilt_zenith=0.2)],
+    "labelfree_coherent": [lf(na_ill=0.0)],
+    "fluorescence": [op.Optics(model=op.FLUOR_3D, nz=8, ny=96, nx=128, dz=0.25, dy=0.1, dx=0.1,
+                               wavelength=0.52, na_ill=0.0, na_det=0.8, n_medium=1.33)],
+    "pol5": [op.Optics(model=op.POL5_3D, nz=8, ny=96, nx=128, dz=0.25, dy=0.1, dx=0.1,
+                       wavelength=0.532, na_ill=0.5, na_det=0.75, n_medium=1.33, swing=0.1)],
+    "sectors9_tilt": [op.Optics(model=op.SECTORS9_3D, nz=8, ny=96, nx=128, dz=0.2, dy=0.1, dx=0.1,
+                                wavelength=0.532, na_ill=0.5, na_det=1.2, n_medium=1.33,
+                                tilt_zenith=0.2, tilt_azimuth=-0.7, edge_width=0.5)],
+}
+
+
+def support_extent(mask):
+    """Largest |frequency index| along y and x of the True entries of [Y][X]."""
+    Y, X = mask.shape
+    ys, xs = np.nonzero(mask)
+    return np.minimum(ys, Y - ys).max(), np.minimum(xs, X - xs).max()
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_support_contains_oracle_bank_and_fields(name):
+    opts = CASES[name]
+    o0 = opts[0]
+    fc, tc, nb = api.lateral_support(opts)
+    Xh = o0.nx // 2 + 1
+    assert fc % 16 == 0 or fc == o0.nx
+    assert tc % 16 == 0 or tc == Xh
+    assert nb % 2 == 1 or nb == o0.ny
+    ky = (nb - 1) // 2 if nb < o0.ny else o0.ny
+    bank_y = bank_x = pupil_x = 0
+    for o in opts:
+        bank = tfm.transfer_function(o)
+        mag = np.abs(bank).max(axis=tuple(range(bank.ndim - 2)))
+        my, mx = support_extent(mag > 1e-9 * mag.max())
+        bank_y, bank_x = max(bank_y, my), max(bank_x, mx)
+        _, px = support_extent(np.abs(op.detection_pupil(o)) > 0)
+        pupil_x = max(pupil_x, px)
+    # contains: every nonzero of the bank and of the pupil's columns is kept
+    assert bank_x < tc and bank_y <= ky
+    if fc < o0.nx:
+        assert 2 * pupil_x + 1 <= fc
+    # tight: at most one spare plus the rounding to 16 (the oracle's bank is a
+    # correlation, so its faint outer ring may sit one index inside the bound)
+    assert tc == Xh or tc - (bank_x + 1) < 16 + 2
+    assert nb == o0.ny or ky - bank_y <= 3
+    if fc < o0.nx:
+        assert fc - (2 * pupil_x + 1) < 16 + 2
+
+
+def test_support_filling_the_grid_is_the_full_layout():
+    o = lf(nx=16, ny=16, dy=0.15, dx=0.15)
+    fc, tc, nb = api.lateral_support([o])
+    assert (fc, tc, nb) == (16, 9, 16)
