@@ -39,16 +39,17 @@ ETA_REL = 1e-3
 def kernel_bytes(name, Z, Y, X, sup, C=1, P=2):
     """Algorithmic HBM bytes one launch of each kernel must move in this step.
 
-    sup = (field columns, bank half-spectrum columns kt, band rows nb) of the
-    lateral support (wo_lateral_support): the fields are kept on the detection
-    pupil's columns, the bank and the spectra on the columns k < kt of every row
-    (of the band rows once transformed along Y)."""
-    fc, kt, nb = sup
+    sup = (field columns, bank half-spectrum columns kt, band rows nb, (ly, lx))
+    of the lateral support (wo_lateral_support): the fields are kept on the
+    detection pupil's columns at ly points along y, the bank and the spectra on
+    the columns k < kt of every row (of the band rows once transformed along Y)."""
+    fc, kt, nb, (ly, _) = sup
     Xh = X // 2 + 1
     cplx = 8
     full = Z * Y * X
     rows_kt = Z * Y * kt          # compact half spectrum, every row
     band = Z * nb * kt            # compact half spectrum, band rows
+    tf_rows = Z * ly * kt         # compact TF before its Y transform (ly rows)
     table = {
         # reconstruction
         "k_rows_r2c": C * (4 * full + cplx * rows_kt),
@@ -57,9 +58,9 @@ def kernel_bytes(name, Z, Y, X, sup, C=1, P=2):
         "k_cols_y_inv": P * cplx * (band + rows_kt),
         "k_rows_c2r": P * (cplx * rows_kt + 4 * full),
         # transfer-function synthesis
-        "k_tf_fields_y": 2 * cplx * Z * Y * fc,
-        "k_tf_rows_lf": 2 * cplx * Z * Y * fc + 2 * cplx * rows_kt,
-        "k_cols_y_tf": 2 * 2 * cplx * rows_kt,
+        "k_tf_fields_y": 2 * cplx * Z * ly * fc,
+        "k_tf_rows_lf": 2 * cplx * Z * ly * fc + 2 * cplx * tf_rows,
+        "k_cols_y_tf": 2 * cplx * (tf_rows + band),
         # band rows' Z transform, plus the zeros of the rest of the bank
         "k_cols_expand": 2 * 2 * cplx * band + 2 * cplx * (Z * Y * Xh - band),
     }
@@ -238,7 +239,7 @@ def main():
     o = api.Optics(**WORKLOAD)
     Z, Y, X = o.nz, o.ny, o.nx
     V = Z * Y * X
-    sup = api.lateral_support([o])
+    sup = api.lateral_support([o], lengths=True)
 
     # ---- inputs (untimed): specimen, forward model on the GPU, noise on the host
     t0 = time.time()
@@ -386,7 +387,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "label-free 3D phase+absorption, 96x512x512, 1 channel x 2 properties",
                    "shape_zyx": [Z, Y, X], "voxel_um": [o.dz, o.dy, o.dx], "eta_rel": ETA_REL},
-        "lateral_support": {"field_cols": sup[0], "tf_cols": sup[1], "band_rows": sup[2]},
+        "lateral_support": {"field_cols": sup[0], "tf_cols": sup[1], "band_rows": sup[2],
+                            "tf_transform_yx": list(sup[3])},
         "reconstruct_cached_tf": {"ms": ms_rec, "voxels_per_s": V / (ms_rec * 1e-3)},
         "fft_schedules": tuner,
         "roofline": roof,

@@ -144,12 +144,15 @@ int wo_transfer_function(const wo_optics* o, int32_t n, void* tf_out, void* ws, 
  * kept by the transfer-function synthesis (nx: all); *tf_cols: the bank's
  * half-spectrum columns k < tf_cols that can be nonzero; *band_rows: its rows
  * y <= ky or y >= ny - ky, band_rows = 2 ky + 1 (ny: all rows).  Bounds keep one
- * spare column or row and are rounded up to multiples of 16.  The 3D linear
- * calls (wo_forward, wo_reconstruct, wo_adjoint) read the bank only there and
- * take it as zero elsewhere, as wo_transfer_function writes it.  Outputs may
- * be NULL. */
+ * spare column or row and are rounded up to multiples of 16.  tf_lengths[0..1]:
+ * the (y, x) transform lengths of the synthesis -- the bank is a correlation
+ * of the fields' spectra, so lengths beyond its extent give it exactly; the
+ * label-free 3D models use the shortest compiled lengths that hold it, the
+ * others (ny, nx).  The 3D linear calls (wo_forward, wo_reconstruct,
+ * wo_adjoint) read the bank only within the support and take it as zero
+ * elsewhere, as wo_transfer_function writes it.  Outputs may be NULL. */
 int wo_lateral_support(const wo_optics* o, int32_t n, int32_t* field_cols, int32_t* tf_cols,
-                       int32_t* band_rows);
+                       int32_t* band_rows, int32_t* tf_lengths);
 
 /* Forward model D_c = sum_p H_cp F_p + N b_c delta(nu), d_c = IFFT(D_c)
  * (Methods, "Linear contrast-separable shift-invariant imaging systems").

@@ -112,7 +112,7 @@ def load(path: str = LIB_PATH):
     lib.wo_workspace_size.argtypes = [op, i32, i32]
     lib.wo_workspace_size.restype = sz
     lib.wo_lateral_support.argtypes = [op, i32, ctypes.POINTER(i32), ctypes.POINTER(i32),
-                                       ctypes.POINTER(i32)]
+                                       ctypes.POINTER(i32), ctypes.POINTER(i32)]
     lib.wo_transfer_function.argtypes = [op, i32, vp, vp, sz, vp]
     lib.wo_forward.argtypes = [op, i32, vp, vp, vp, vp, vp, sz, vp]
     lib.wo_reconstruct.argtypes = [op, i32, vp, vp, vp, ctypes.c_double, vp, vp, sz, vp]
@@ -199,14 +199,18 @@ def bank_shape(optics):
     return C.value, P.value, dims.value, n.value
 
 
-def lateral_support(optics):
+def lateral_support(optics, lengths=False):
     """(field columns, bank half-spectrum columns, band rows) of the model's lateral
-    support for these patches (wo_lateral_support)."""
+    support for these patches, plus the synthesis' (y, x) transform lengths when
+    `lengths` (wo_lateral_support)."""
     lib = load()
     arr = optics_array(optics)
     fc, tc, br = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
-    _check(lib.wo_lateral_support(arr, len(arr), ctypes.byref(fc), ctypes.byref(tc), ctypes.byref(br)),
+    tl = (ctypes.c_int32 * 2)()
+    _check(lib.wo_lateral_support(arr, len(arr), ctypes.byref(fc), ctypes.byref(tc), ctypes.byref(br), tl),
            "wo_lateral_support")
+    if lengths:
+        return fc.value, tc.value, br.value, (tl[0], tl[1])
     return fc.value, tc.value, br.value
 
 

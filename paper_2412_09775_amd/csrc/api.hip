@@ -323,7 +323,47 @@ LatSupport lateral_support(const wo_optics* o, int32_t n) {
   const int kt = (px + ax + 1 + 15) / 16 * 16;
   if (kt < Xh) ls.kt = kt;
   if (2 * (py + ay) + 1 < Y) ls.ky = py + ay;
+  // Shortest transform lengths with compiled stages that hold the
+  // correlation without wrap-around (at least 2 (p + a) + 1 points), the kept
+  // columns of the fields and, along X, the kept columns of the result as
+  // non-negative frequencies.
+  auto length_for = [](int need, int full) {
+    static const int sizes[] = {64, 128, 160, 192, 240, 256, 320, 384, 480, 512, 1024};
+    for (int n : sizes)
+      if (n >= need && n < full) return n;
+    return full;
+  };
+  ls.lx = length_for(std::max(std::max(2 * (px + ax) + 1, 2 * (ls.kt - 1)), ls.xc), X);
+  ls.ly = ls.ky < Y ? length_for(2 * ls.ky + 1, Y) : Y;
   return ls;
+}
+
+// Complex values of the compact fields of nv field sets, rounded up to 256 bytes.
+long compact_fields_elems(int nv, int nf, const Shape& s, const LatSupport& sup) {
+  return ((long)nv * nf * s.Z * sup.ly * sup.xc + 31) / 32 * 32;
+}
+
+// The support the transfer-function synthesis works on.  The label-free 3D
+// models (one or nine apertures) keep the bank in its support until the Z
+// pass, in a compact copy behind the compact fields (*compact_out) when both
+// fit the field buffer; the others write their bank in place on the grid's
+// own transform lengths.
+LatSupport tf_support(const wo_optics* o, int32_t n, const Shape& s, bool* compact_out) {
+  const Sampling sm = sampling_of(o);
+  LatSupport sup = o->model == WO_MODEL_FLUOR_3D ? full_support(sm) : lateral_support(o, n);
+  const int nf = o->model == WO_MODEL_FLUOR_3D ? 1 : 2;
+  const int nv = n * field_sets(o);
+  const int P3 = o->model == WO_MODEL_SECTORS9_3D ? 1 : 2;
+  const long cplane = (long)sup.ly * sup.kt;
+  *compact_out = (o->model == WO_MODEL_LABELFREE_3D || o->model == WO_MODEL_SECTORS9_3D) &&
+                 (sup.kt < s.Xh || sup.ky < s.Y) &&
+                 compact_fields_elems(nv, nf, s, sup) + (long)nv * P3 * s.Z * cplane <=
+                     (long)nv * nf * s.Z * s.Y * s.X;
+  if (!*compact_out) {
+    sup.ly = (int)s.Y;
+    sup.lx = (int)s.X;
+  }
+  return sup;
 }
 
 size_t tf_ws(const wo_optics* o, int32_t n, const Shape& s) {
@@ -1007,14 +1047,22 @@ size_t wo_workspace_size(const wo_optics* o, int32_t n, int32_t op) {
 }
 
 int wo_lateral_support(const wo_optics* o, int32_t n, int32_t* field_cols, int32_t* tf_cols,
-                       int32_t* band_rows) {
+                       int32_t* band_rows, int32_t* tf_lengths) {
   int st = validate(o, n);
   if (st) return st;
+  Shape s;
+  if (!bank_shape(o, &s)) return WO_EINVAL;
   const LatSupport ls = lateral_support(o, n);
+  bool compact_out = false;
+  const LatSupport ts = tf_support(o, n, s, &compact_out);
   const int nb = ls.ky >= o->ny ? o->ny : 2 * ls.ky + 1;
-  if (field_cols) *field_cols = o->model == WO_MODEL_FLUOR_3D ? o->nx : ls.xc;
+  if (field_cols) *field_cols = ts.xc;
   if (tf_cols) *tf_cols = ls.kt;
   if (band_rows) *band_rows = nb;
+  if (tf_lengths) {
+    tf_lengths[0] = ts.ly;
+    tf_lengths[1] = ts.lx;
+  }
   return WO_OK;
 }
 
@@ -1053,19 +1101,14 @@ int wo_transfer_function(const wo_optics* o, int32_t n, void* tf_out, void* ws, 
   // in its support (columns kx < kt, band rows) until the Z pass, which
   // writes the full bank (zeros outside), when that compact copy fits the
   // field buffer behind the compact fields.
-  LatSupport sup = o->model == WO_MODEL_FLUOR_3D ? full_support(sm) : lateral_support(o, n);
-  WO_TRY(launch_tf_fields_y(dopt, sm, nv, ab, partials, hs, &sup));
+  bool compact_out = false;
+  LatSupport sup = tf_support(o, n, s, &compact_out);
   float2* tf = (float2*)tf_out;
   const long M = s.Y * s.Xh;
   const long plane = s.Y * s.Xh;
-  const long fields = (long)nv * nf * s.Z * s.Y * sup.xc;
-  const long cplane = s.Y * (long)sup.kt;
-  const int P3 = o->model == WO_MODEL_SECTORS9_3D ? 1 : 2;
-  float2* cb = ab + (fields + 31) / 32 * 32;
-  const bool compact_out = (o->model == WO_MODEL_LABELFREE_3D || o->model == WO_MODEL_SECTORS9_3D) &&
-                           (sup.kt < s.Xh || sup.ky < s.Y) &&
-                           (fields + 31) / 32 * 32 + (long)nv * P3 * s.Z * cplane <=
-                               (long)nv * nf * s.Z * s.Y * s.X;
+  const long cplane = (long)sup.ly * sup.kt;   // a compact plane: ly rows of kt columns
+  float2* cb = ab + compact_fields_elems(nv, nf, s, sup);
+  WO_TRY(launch_tf_fields_y(dopt, sm, nv, ab, partials, hs, &sup));
   LatSupport full_out = sup;
   full_out.kt = (int)s.Xh;
   switch (o->model) {
@@ -1078,8 +1121,9 @@ int wo_transfer_function(const wo_optics* o, int32_t n, void* tf_out, void* ws, 
       if (compact_out) {
         WO_TRY(launch_tf_rows_labelfree(partials, sm, n, ab, cb, 2 * s.Z * cplane, s.Z * cplane, cplane,
                                         hs, &sup, sup.kt));
-        WO_TRY(launch_cols(cb, (int)s.Y, sup.kt, 2 * s.Z, 2 * s.Z, n, -1.f, hs, "k_cols_y_tf", 1, sup.ky));
-        WO_TRY(launch_cols_expand(cb, tf, (int)s.Z, (int)s.Y, (int)s.Xh, sup.kt, sup.ky, 2L * n, -1.f, hs));
+        WO_TRY(launch_cols(cb, sup.ly, sup.kt, 2 * s.Z, 2 * s.Z, n, -1.f, hs, "k_cols_y_tf", 1, sup.ky));
+        WO_TRY(launch_cols_expand(cb, tf, (int)s.Z, sup.ly, (int)s.Y, (int)s.Xh, sup.kt, sup.ky, 2L * n,
+                                  -1.f, hs));
       } else {
         WO_TRY(launch_tf_rows_labelfree(partials, sm, n, ab, tf, 2 * s.Z * plane, s.Z * plane, plane, hs,
                                         &full_out));
@@ -1097,8 +1141,9 @@ int wo_transfer_function(const wo_optics* o, int32_t n, void* tf_out, void* ws, 
       if (compact_out) {
         WO_TRY(launch_tf_rows_labelfree(partials, sm, nv, ab, cb, s.Z * cplane, -1, cplane, hs, &sup,
                                         sup.kt));
-        WO_TRY(launch_cols(cb, (int)s.Y, sup.kt, s.Z, s.Z, nv, -1.f, hs, "k_cols_y_tf", 1, sup.ky));
-        WO_TRY(launch_cols_expand(cb, tf, (int)s.Z, (int)s.Y, (int)s.Xh, sup.kt, sup.ky, nv, -1.f, hs));
+        WO_TRY(launch_cols(cb, sup.ly, sup.kt, s.Z, s.Z, nv, -1.f, hs, "k_cols_y_tf", 1, sup.ky));
+        WO_TRY(launch_cols_expand(cb, tf, (int)s.Z, sup.ly, (int)s.Y, (int)s.Xh, sup.kt, sup.ky, nv, -1.f,
+                                  hs));
       } else {
         WO_TRY(launch_tf_rows_labelfree(partials, sm, nv, ab, tf, s.Z * plane, -1, plane, hs, &full_out));
         WO_TRY(launch_cols(tf, (int)s.Y, s.Xh, s.Z, s.Z, nv, -1.f, hs, "k_cols_y_tf"));

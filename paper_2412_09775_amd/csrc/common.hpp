@@ -146,12 +146,30 @@ __device__ __forceinline__ void dft8(float2* v, float s) {
   }
 }
 
+// 6 = 2 x 3: DFTs of the even and odd samples, E and O, then
+// X[k] = E[k] + W6^k O[k] and X[k + 3] = E[k] - W6^k O[k], W6 = exp(s i pi / 3).
+__device__ __forceinline__ void dft6(float2* v, float s) {
+  const float h = 0.86602540378443864676f;  // sin(pi / 3)
+  float2 e[3] = {v[0], v[2], v[4]}, o[3] = {v[1], v[3], v[5]};
+  dft3(e, s);
+  dft3(o, s);
+  const float2 t1 = make_float2(0.5f * o[1].x - s * h * o[1].y, 0.5f * o[1].y + s * h * o[1].x);
+  const float2 t2 = make_float2(-0.5f * o[2].x - s * h * o[2].y, -0.5f * o[2].y + s * h * o[2].x);
+  v[0] = cadd(e[0], o[0]);
+  v[3] = csub(e[0], o[0]);
+  v[1] = cadd(e[1], t1);
+  v[4] = csub(e[1], t1);
+  v[2] = cadd(e[2], t2);
+  v[5] = csub(e[2], t2);
+}
+
 template <int R>
 __device__ __forceinline__ void dft_small(float2* v, float s) {
   if constexpr (R == 2) dft2(v);
   else if constexpr (R == 3) dft3(v, s);
   else if constexpr (R == 4) dft4(v, s);
   else if constexpr (R == 5) dft5(v, s);
+  else if constexpr (R == 6) dft6(v, s);
   else if constexpr (R == 8) dft8(v, s);
 }
 
@@ -595,10 +613,13 @@ namespace wo {
 
 template <int N>
 struct StaticPlan {
+  // radices in the order 8, 4, 6, 2, 3, 5: a radix-6 butterfly (two radix-3
+  // DFTs in registers) replaces a radix-2 and a radix-3 pass, one LDS round
+  // trip fewer (384 = 8 8 6, 240 = 8 6 5, 48 = 8 6)
   static constexpr int radix(int q) {
     int m = N, p = 0;
-    const int order[5] = {8, 4, 2, 3, 5};
-    for (int i = 0; i < 5; ++i) {
+    const int order[6] = {8, 4, 6, 2, 3, 5};
+    for (int i = 0; i < 6; ++i) {
       const int f = order[i];
       while (m % f == 0) {
         if (p == q) return f;

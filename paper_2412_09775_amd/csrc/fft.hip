@@ -395,14 +395,16 @@ hipError_t launch_cols(float2* data, int N, long M, long planes_per_group, long 
 }
 
 // FFT along N of the columns kx < kt of the band rows, from compact planes
-// src [g][N][Y][kt] into full planes dst [g][N][Y][Xh].  Workgroup: W
+// src [g][N][Ys][kt] into full planes dst [g][N][Y][Xh] (band row b is row
+// band_row(b, .., Ys) of a source plane and band_row(b, .., Y) of a
+// destination plane).  Workgroup: W
 // consecutive columns of one band row of one plane group.  While its loads
 // are in flight a workgroup also writes the zeros of its share (zrows rows
 // from bid * zrows) of the rest of dst: rows outside the band, columns kx >= kt.
 template <int NS, int WS>
 __global__ __launch_bounds__(1024) void k_cols_expand(const float2* __restrict__ src,
-                                                      float2* __restrict__ dst, int N, int Y, int Xh,
-                                                      int kt, int ky, int nb, int Wrt,
+                                                      float2* __restrict__ dst, int N, int Ys, int Y,
+                                                      int Xh, int kt, int ky, int nb, int Wrt,
                                                       int tiles_row, long tiles_g, long zrows,
                                                       long zrows_total, FftPlan plan, float sign) {
   const int W = WS > 0 ? WS : Wrt;   // a power of two
@@ -415,11 +417,11 @@ __global__ __launch_bounds__(1024) void k_cols_expand(const float2* __restrict__
   const long g = bid / tiles_g;
   const long t = bid - g * tiles_g;
   const int b = (int)(t / tiles_row), j = (int)(t - (long)b * tiles_row);
-  const int y = band_row(b, ky, nb, Y);
+  const int ys = band_row(b, ky, nb, Ys), y = band_row(b, ky, nb, Y);
   const int kx0 = j * W;
   const int weff = min(W, kt - kx0);
-  const long ms = (long)Y * kt, md = (long)Y * Xh;   // plane pitches
-  const float2* sb = src + g * N * ms + (long)y * kt + kx0;
+  const long ms = (long)Ys * kt, md = (long)Y * Xh;   // plane pitches
+  const float2* sb = src + g * N * ms + (long)ys * kt + kx0;
   float2* db = dst + g * N * md + (long)y * Xh + kx0;
   const int Nc = NS > 0 ? NS : N;
   auto mid = [&] {
@@ -453,10 +455,11 @@ __global__ __launch_bounds__(1024) void k_cols_expand(const float2* __restrict__
   }
 }
 
-hipError_t launch_cols_expand(const float2* src, float2* dst, int N, int Y, int Xh, int kt, int ky,
-                              long ngroups, float sign, hipStream_t s) {
-  if (kt < 1 || kt > Xh || ky < 0) return hipErrorInvalidValue;
+hipError_t launch_cols_expand(const float2* src, float2* dst, int N, int Ys, int Y, int Xh, int kt,
+                              int ky, long ngroups, float sign, hipStream_t s) {
+  if (kt < 1 || kt > Xh || ky < 0 || Ys < 1 || Ys > Y) return hipErrorInvalidValue;
   const int nb = 2L * ky + 1 < Y ? 2 * ky + 1 : Y;
+  if (nb > Ys || (nb == Y && Ys != Y)) return hipErrorInvalidValue;   // the band fits both
   const int kyn = nb == Y ? Y : ky;
   const FftChoice c = cols_default(N);
   FftPlan plan;
@@ -474,11 +477,12 @@ hipError_t launch_cols_expand(const float2* src, float2* dst, int N, int Y, int 
   case NN:                                                                                      \
     if (W == static_tile_width(NN))                                                             \
       hipLaunchKernelGGL((k_cols_expand<NN, static_tile_width(NN)>), dim3((unsigned)nwg), dim3(thr), \
-                         lds, s, src, dst, N, Y, Xh, kt, kyn, nb, W, tiles_row, tiles_g, zrows,  \
-                         zrows_total, plan, sign);                                              \
+                         lds, s, src, dst, N, Ys, Y, Xh, kt, kyn, nb, W, tiles_row, tiles_g,     \
+                         zrows, zrows_total, plan, sign);                                       \
     else                                                                                        \
       hipLaunchKernelGGL((k_cols_expand<NN, 0>), dim3((unsigned)nwg), dim3(thr), lds, s, src, dst, N, \
-                         Y, Xh, kt, kyn, nb, W, tiles_row, tiles_g, zrows, zrows_total, plan, sign); \
+                         Ys, Y, Xh, kt, kyn, nb, W, tiles_row, tiles_g, zrows, zrows_total, plan,   \
+                         sign);                                                                 \
     return hipGetLastError();
   if (c.plan == 0) switch (N) {
       WO_AXIAL_SIZES(X_)
@@ -486,8 +490,8 @@ hipError_t launch_cols_expand(const float2* src, float2* dst, int N, int Y, int 
         break;
     }
 #undef X_
-  hipLaunchKernelGGL((k_cols_expand<0, 0>), dim3((unsigned)nwg), dim3(thr), lds, s, src, dst, N, Y, Xh,
-                     kt, kyn, nb, W, tiles_row, tiles_g, zrows, zrows_total, plan, sign);
+  hipLaunchKernelGGL((k_cols_expand<0, 0>), dim3((unsigned)nwg), dim3(thr), lds, s, src, dst, N, Ys, Y,
+                     Xh, kt, kyn, nb, W, tiles_row, tiles_g, zrows, zrows_total, plan, sign);
   return hipGetLastError();
 }
 

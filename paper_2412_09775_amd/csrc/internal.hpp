@@ -114,11 +114,12 @@ hipError_t launch_rows_c2r(const float2* in, float* out, int X, const RowGroups&
 hipError_t launch_cols(float2* data, int N, long M, long planes_per_group, long group_stride,
                        long ngroups, float sign, hipStream_t s, const char* tag = "k_cols",
                        int band = 0, int ky = -1);
-// FFT along N of the band rows of compact planes src [g][N][Y][kt] into the
-// full half-spectrum planes dst [g][N][Y][Xh]; every other value of dst (rows
-// outside the band, columns kx >= kt) is set to zero.
-hipError_t launch_cols_expand(const float2* src, float2* dst, int N, int Y, int Xh, int kt, int ky,
-                              long ngroups, float sign, hipStream_t s);
+// FFT along N of the band rows (y <= ky or y >= rows - ky) of compact planes
+// src [g][N][Ys][kt] into the full half-spectrum planes dst [g][N][Y][Xh];
+// every other value of dst (rows outside the band, columns kx >= kt) is set
+// to zero.
+hipError_t launch_cols_expand(const float2* src, float2* dst, int N, int Ys, int Y, int Xh, int kt,
+                              int ky, long ngroups, float sign, hipStream_t s);
 
 enum SpectralMode { kModeForward = 0, kModeSolve = 1, kModeAdjoint = 2 };
 
@@ -153,17 +154,22 @@ hipError_t launch_set_params(DevOptics* dst, const DevOptics* host, int n, hipSt
 // function's half-spectrum columns kx < kt; the band Z pass transforms rows
 // y <= ky or y >= Y - ky (ky = Y: every row).  full_support is the plain
 // layout.
+// The label-free transfer function is the 2D correlation of the fields' spectra
+// A and B, so a transform of ly x lx points (at least the correlation's
+// extent) yields it exactly: the field kernel's inverse Y transform has ly
+// points, the row kernel's X transforms lx (ly = ny, lx = nx: the grid's own).
 struct LatSupport {
   int xc, kp;
   int kt;
   int ky;
+  int ly, lx;
 };
 inline LatSupport full_support(const Sampling& sm) {
-  return LatSupport{sm.nx, sm.nx - 1, sm.nx / 2 + 1, sm.ny};
+  return LatSupport{sm.nx, sm.nx - 1, sm.nx / 2 + 1, sm.ny, sm.ny, sm.nx};
 }
-// Column tile width of the field kernel; the pupil-sum partials hold
-// ceil(xc / width) doubles per patch.
-int tf_tile_width(const Sampling& sm);
+// Column tile width of the field kernel for a transform of ly points (0: ny);
+// the pupil-sum partials hold ceil(xc / width) doubles per patch.
+int tf_tile_width(const Sampling& sm, int ly = 0);
 // Planes per workgroup of the z-chunked field and gradient kernels.
 int tf_z_chunk(const Sampling& sm, long tiles_x, long npatch, long target);
 hipError_t launch_tf_fields_y(const DevOptics* opt, const Sampling& sm, int npatch, float2* ab,

@@ -81,7 +81,11 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
 
 // ab layout: [patch][field][z][y][c] complex (field 0 = A or the fluorescence
 // field, field 1 = B), c the compact column of the lateral frequency kx (see
-// field_column; c = kx when XC = X).  A workgroup owns one column tile of one patch and a
+// field_column; c = kx when XC = X), y one of the LY points of the inverse Y
+// transform.  LY = Y is the grid's own transform; a shorter LY (still longer
+// than twice the support's extent along y) samples the same band-limited
+// fields more coarsely: frequency index i of the LY-point transform stands for
+// the grid's frequency (i or i - LY) / (Y dy).  A workgroup owns one column tile of one patch and a
 // chunk of ZC consecutive planes: the pupil values, which do not depend on z,
 // are evaluated once into registers; each plane then only needs its phase.
 // The workgroup of the first chunk also writes the tile's share of the pupil
@@ -91,11 +95,14 @@ template <int NS, int NF, bool AB>
 __global__ __launch_bounds__(1024) void k_tf_fields_y(const DevOptics* __restrict__ opt,
                                                       Sampling sm, float2* __restrict__ ab,
                                                       double* __restrict__ partials, int W,
-                                                      long tiles_x, int ZC, int XC, int KP,
+                                                      long tiles_x, int ZC, int XC, int KP, int LY,
                                                       FftPlan plan) {
   __shared__ double red[kMaxThreads / 64];
   extern __shared__ float2 smem[];
-  const int Y = sm.ny, X = sm.nx, Z = sm.nz;
+  const int Y = NS > 0 ? NS : LY;   // transform length
+  const int X = sm.nx, Z = sm.nz;
+  // frequency of transform index i: the grid's spacing 1 / (ny dy), wrapped at Y
+  auto freq_y = [&](int i) { return (double)(i < (Y + 1) / 2 ? i : i - Y) / ((double)sm.ny * sm.dy); };
   float2* tw = smem;
   float2* buf = smem + Y;
   const int tid = threadIdx.x, nthr = blockDim.x;
@@ -148,7 +155,7 @@ __global__ __launch_bounds__(1024) void k_tf_fields_y(const DevOptics* __restric
           if constexpr (AB) ab2[b][r] = 0.f;
           if (j < nl * NB0 && c < XC) {
             const int ky = k + r * NB0;
-            const double fy = fftfreq(ky, Y, sm.dy), fx = fftfreq(kx, X, sm.dx);
+            const double fy = freq_y(ky), fx = fftfreq(kx, X, sm.dx);
             const double P = disc(fy, fx, rd, hw);
             if (P != 0.0) {
               const double kz = sqrt(fmax(km * km - (fy * fy + fx * fx), 0.0));
@@ -257,7 +264,7 @@ __global__ __launch_bounds__(1024) void k_tf_fields_y(const DevOptics* __restric
           const int c = x0 + w;
           const int kx = field_column(c, KP, X, XC);
           if (c < XC) {
-            const double fy = fftfreq(ky, Y, sm.dy), fx = fftfreq(kx, X, sm.dx);
+            const double fy = freq_y(ky), fx = fftfreq(kx, X, sm.dx);
             const double P = disc(fy, fx, rd, hw);
             if (P != 0.0) {
               const double kz = sqrt(fmax(km * km - (fy * fy + fx * fx), 0.0));
@@ -338,31 +345,38 @@ int tf_z_chunk(const Sampling& sm, long tiles_x, long npatch, long target) {
 // plane, so several smaller workgroups per CU hide those waits better than
 // one large one (measured: 96x512x512, 8 columns x 2 fields 169 us, 4 columns
 // 135 us).
-int tf_tile_width(const Sampling& sm) {
+int tf_tile_width(const Sampling& sm, int ly) {
   const int nf = sm.model == kFluor3D ? 1 : 2;
+  const long n = ly > 0 ? ly : sm.ny;
   const long lim = lds_limit_bytes() / (long)sizeof(float2);
   int W = 16;
-  while (W > 1 && ((long)W * nf * sm.ny > 4096 || sm.ny + (long)W * nf * sm.ny > lim)) W /= 2;
+  while (W > 1 && ((long)W * nf * n > 4096 || n + (long)W * nf * n > lim)) W /= 2;
   return W;
 }
 
 hipError_t launch_tf_fields_y(const DevOptics* opt, const Sampling& sm, int npatch, float2* ab,
                               double* partials, hipStream_t s, const LatSupport* sup) {
-  FftPlan plan;
-  if (!make_plan(sm.ny, &plan)) return hipErrorInvalidValue;
   const LatSupport ls = sup ? *sup : full_support(sm);
-  if (ls.xc < 1 || ls.xc > sm.nx || ls.kp < 0 || ls.kp >= ls.xc) return hipErrorInvalidValue;
+  if (ls.xc < 1 || ls.xc > sm.nx || ls.kp < 0 || ls.kp >= ls.xc || ls.ly < 2 || ls.ly > sm.ny)
+    return hipErrorInvalidValue;
+  const int LY = ls.ly;
+  FftPlan plan;
+  if (!make_plan(LY, &plan)) return hipErrorInvalidValue;
   const int nf = sm.model == kFluor3D ? 1 : 2;
-  const int W = tf_tile_width(sm);
+  const int W = tf_tile_width(sm, LY);
   const long tiles = (ls.xc + W - 1) / W;
-  const int ZC = tf_z_chunk(sm, tiles, npatch, 2048);
+  // about 256 workgroups: each evaluates the z-independent pupil factors of
+  // its tile once (FP64 square roots and divisions) and reuses them for up to
+  // 16 planes (96x512x512, 60 tiles: 93 us with 2 planes per workgroup, 70 us
+  // with 16)
+  const int ZC = tf_z_chunk(sm, tiles, npatch, 256);
   const long nwg = tiles * ((sm.nz + ZC - 1) / ZC) * (long)npatch;
-  const int thr = threads_for((long)sm.ny * nf * W);
-  const size_t lds = (size_t)(sm.ny + sm.ny * nf * W) * sizeof(float2);
+  const int thr = threads_for((long)LY * nf * W);
+  const size_t lds = (size_t)(LY + LY * nf * W) * sizeof(float2);
   ScopedTiming _t("k_tf_fields_y", s);
 #define WO_FIELDS(NN, FF, AA)                                                                    \
   hipLaunchKernelGGL((k_tf_fields_y<NN, FF, AA>), dim3((unsigned)nwg), dim3(thr), lds, s, opt, sm, ab, \
-                     partials, W, tiles, ZC, ls.xc, ls.kp, plan)
+                     partials, W, tiles, ZC, ls.xc, ls.kp, LY, plan)
 #define X_(NN)                                                                                   \
   case NN:                                                                                       \
     if (nf == 2) {                                                                               \
@@ -371,7 +385,7 @@ hipError_t launch_tf_fields_y(const DevOptics* opt, const Sampling& sm, int npat
       if (sm.aberrated) WO_FIELDS(NN, 1, true); else WO_FIELDS(NN, 1, false);                    \
     }                                                                                            \
     return hipGetLastError();
-  switch (sm.ny) {
+  switch (LY) {
     WO_LATERAL_SIZES(X_)
     default:
       break;
@@ -389,9 +403,10 @@ hipError_t launch_tf_fields_y(const DevOptics* opt, const Sampling& sm, int npat
 // ------------------------------------------------------------------ rows: label-free
 
 // out[patch * patch_stride + p * pstride + z * zstride + y * OP + k], k < KT,
-// p = 0 phase, 1 absorption (pstride < 0: phase only).  The fields are read in
-// the compact column layout of the field kernel (XC columns, last
-// non-negative column KP); the columns it does not store are zero.
+// y < LY, p = 0 phase, 1 absorption (pstride < 0: phase only).  The fields are
+// read in the compact column layout of the field kernel (XC columns, last
+// non-negative column KP) and placed on an LX-point transform (frequency kx
+// at index kx or LX + kx); the columns it does not store are zero.
 
 template <int NS>
 __global__ __launch_bounds__(1024) void k_tf_rows_lf(const double* __restrict__ partials,
@@ -400,11 +415,13 @@ __global__ __launch_bounds__(1024) void k_tf_rows_lf(const double* __restrict__ 
                                                      float2* __restrict__ out, long patch_stride,
                                                      long pstride, long zstride, int rows_per_wg,
                                                      long wg_per_patch, int XC, int KP, int KT,
-                                                     int OP, FftPlan plan) {
+                                                     int OP, int LY, int LX, FftPlan plan) {
   __shared__ double ibg_s;
   extern __shared__ float2 smem[];
-  const int Y = sm.ny, Z = sm.nz;
-  const int X = NS > 0 ? NS : sm.nx;   // compile-time length for the index arithmetic
+  // transform lengths: LY rows per plane (the field kernel's), X = LX points
+  // per row (compile-time for the index arithmetic)
+  const int Y = LY, Z = sm.nz;
+  const int X = NS > 0 ? NS : LX;
   float2* tw = smem;
   float2* buf = smem + X;
   const int tid = threadIdx.x, nthr = blockDim.x;
@@ -419,12 +436,14 @@ __global__ __launch_bounds__(1024) void k_tf_rows_lf(const double* __restrict__ 
   const int PS = pad_shift(X);   // row padding
   const int LS = row_stride(X);      // padded line pitch in LDS
   const int neg0 = X - (XC - KP - 1);   // first stored negative-frequency column
-  // line 2r holds a, line 2r + 1 holds b of row r; the condition depends on
-  // the index only, so the loads of a thread stay in flight together
+  // line 2r holds a, line 2r + 1 holds b of row r.  A column the field kernel
+  // does not store loads column KP (a valid address, no branch, so the loads
+  // of a thread stay in flight together) and is zeroed after the loads.
   auto load = [&](int t, int i) {
     const float2* src = ((t & 1) ? b_src : a_src) + (row0 + (t >> 1)) * XC;
-    return (i <= KP || i >= neg0) ? src[i <= KP ? i : i - (X - XC)] : make_float2(0.f, 0.f);
+    return src[i <= KP ? i : max(i - (X - XC), KP)];
   };
+  auto kept = [&](int t, int i, float2 v) { return (i <= KP || i >= neg0) ? v : make_float2(0.f, 0.f); };
   if constexpr (NS > 0) {
     // Inverse transforms of a and b in reversed radix order, the first pass
     // straight from memory; their last pass, the product c = b conj(a) /
@@ -435,8 +454,8 @@ __global__ __launch_bounds__(1024) void k_tf_rows_lf(const double* __restrict__ 
     constexpr int R0 = StaticPlan<NS>::radix(0);
     constexpr int NB = NS / R0;
     constexpr int BPF = (kEmax + 2 * R0 - 1) / (2 * R0);   // butterflies of a thread
-    first_pass_in<NS, 0, false, kEmax, true, true>(
-        buf, 2 * nr, 1, LS, -1, 1.f, tid, nthr, load,
+    first_pass_in2<NS, 0, false, kEmax, true, true>(
+        buf, 2 * nr, 1, LS, -1, 1.f, tid, nthr, load, kept,
         [&] { wave0_sum(partials + patch * tiles_x, tiles_x, &ibg_s); });   // sum S P^2
     const float cs = (float)(1.0 / ((double)X * (double)Y * ibg_s));
     static_passes<NS, 0, false, kEmax, true, true, 1, NP - 1>(buf, 2 * nr, 1, LS, -1, tw, 1.f, tid,
@@ -489,8 +508,8 @@ __global__ __launch_bounds__(1024) void k_tf_rows_lf(const double* __restrict__ 
     static_passes<NS, 0, false, kEmax, true, false, 1, NP>(buf, nr, 1, 2 * LS, -1, tw, -1.f, tid, nthr);
   } else {
     gather_to_lds_map(buf, nr * 2 * X, tid, nthr, [&](int e) {
-      const int t = e / X;
-      return load(t, e - t * X);
+      const int t = e / X, i = e - t * X;
+      return kept(t, i, load(t, i));
     }, [&](int e) {
       const int t = e / X;
       return t * LS + row_slot(e - t * X, PS);
@@ -544,43 +563,45 @@ hipError_t launch_tf_rows_labelfree(const double* partials, const Sampling& sm, 
                                     long pstride, long zstride, hipStream_t s,
                                     const LatSupport* sup, int pitch) {
   const LatSupport ls = sup ? *sup : full_support(sm);
-  const int Xh = sm.nx / 2 + 1;
-  if (ls.xc < 1 || ls.xc > sm.nx || ls.kp < 0 || ls.kp >= ls.xc || ls.kt < 1 || ls.kt > Xh)
+  const int LX = ls.lx, LY = ls.ly;
+  if (ls.xc < 1 || ls.xc > LX || ls.kp < 0 || ls.kp >= ls.xc || ls.kt < 1 || 2 * (ls.kt - 1) > LX ||
+      LX > sm.nx || LY < 2 || LY > sm.ny)
     return hipErrorInvalidValue;
-  const int OP = pitch > 0 ? pitch : Xh;
+  const int OP = pitch > 0 ? pitch : sm.nx / 2 + 1;
   if (OP < ls.kt) return hipErrorInvalidValue;
-  const FftKey key{kFftTfRows, sm.nx, sm.ny, (long)npatch * sm.nz, pstride < 0 ? 1 : 0};
+  const FftKey key{kFftTfRows, LX, LY, (long)npatch * sm.nz, pstride < 0 ? 1 : 0};
   if (fft_recording())
     fft_record(key, [=] {
       return launch_tf_rows_labelfree(partials, sm, npatch, ab, out, patch_stride, pstride, zstride, s,
                                       &ls, OP);
     });
   FftChoice c;
-  if (!fft_lookup(key, &c) || !tf_rows_choice_ok(sm.nx, c)) c = tf_rows_default(sm.nx);
-  const long tiles_x = (ls.xc + tf_tile_width(sm) - 1) / tf_tile_width(sm);
+  if (!fft_lookup(key, &c) || !tf_rows_choice_ok(LX, c)) c = tf_rows_default(LX);
+  const long tiles_x = (ls.xc + tf_tile_width(sm, LY) - 1) / tf_tile_width(sm, LY);
   FftPlan plan;
-  if (!make_plan_variant(sm.nx, c.plan, &plan)) return hipErrorInvalidValue;
+  if (!make_plan_variant(LX, c.plan, &plan)) return hipErrorInvalidValue;
   const int R = c.w;
-  const long rpp = (long)sm.nz * sm.ny;
+  const long rpp = (long)sm.nz * LY;
   const long wpp = (rpp + R - 1) / R;
   const long nwg = wpp * npatch;
   const int thr = c.threads;
-  const size_t lds = (size_t)(sm.nx + 2L * R * row_stride(sm.nx)) * sizeof(float2);
+  const size_t lds = (size_t)(LX + 2L * R * row_stride(LX)) * sizeof(float2);
   ScopedTiming _t("k_tf_rows_lf", s);
 #define X_(NN)                                                                                   \
   case NN:                                                                                       \
     hipLaunchKernelGGL((k_tf_rows_lf<NN>), dim3((unsigned)nwg), dim3(thr), lds, s, partials, tiles_x, \
                        sm, ab, out, patch_stride, pstride, zstride, R, wpp, ls.xc, ls.kp, ls.kt, OP, \
-                       plan);                                                                    \
+                       LY, LX, plan);                                                            \
     return hipGetLastError();
-  if (c.plan == 0) switch (sm.nx) {
+  if (c.plan == 0) switch (LX) {
       WO_LATERAL_SIZES(X_)
       default:
         break;
     }
 #undef X_
   hipLaunchKernelGGL((k_tf_rows_lf<0>), dim3((unsigned)nwg), dim3(thr), lds, s, partials, tiles_x, sm,
-                     ab, out, patch_stride, pstride, zstride, R, wpp, ls.xc, ls.kp, ls.kt, OP, plan);
+                     ab, out, patch_stride, pstride, zstride, R, wpp, ls.xc, ls.kp, ls.kt, OP, LY, LX,
+                     plan);
   return hipGetLastError();
 }
 

@@ -107,6 +107,11 @@ CASES = {
                                            edge_width=0.25)],
     "sectors9_band": [sectors(nz=12, ny=96, nx=128, tilt_zenith=0.2, tilt_azimuth=-0.7,
                               edge_width=0.5)],
+    # the correlation's extent well below the grid: the synthesis runs on
+    # shorter transforms (192 x 240 here) than the 256 x 256 grid
+    "labelfree_3d_short_transforms": [labelfree(nz=8, ny=256, nx=256, defocus=-0.2, tilt_zenith=0.2,
+                                                edge_width=0.5)],
+    "sectors9_short_transforms": [sectors(nz=6, ny=256, nx=256, tilt_zenith=0.15, tilt_azimuth=1.1)],
 }
 
 
@@ -232,7 +237,8 @@ def test_adjoint_matches_oracle(gpu_lib, torch, name):
         assert err < TOL_ADJ
 
 
-@pytest.mark.parametrize("name", ["labelfree_3d_band_batch2", "sectors9_band", "labelfree_3d_tilt_soft"])
+@pytest.mark.parametrize("name", ["labelfree_3d_band_batch2", "sectors9_band", "labelfree_3d_tilt_soft",
+                                  "labelfree_3d_short_transforms", "sectors9_short_transforms"])
 def test_transfer_function_elementwise_at_support_edge(gpu_lib, torch, name):
     """Every value, including the faint ring at the edge of the support, within
     1e-5 of the largest (a support bound one column short fails this)."""

@@ -33,7 +33,9 @@ CASES = {
     "sectors9_tilt": [op.Optics(model=op.SECTORS9_3D, nz=8, ny=96, nx=128, dz=0.2, dy=0.1, dx=0.1,
                                 wavelength=0.532, na_ill=0.5, na_det=1.2, n_medium=1.33,
                                 tilt_zenith=0.2, tilt_azimuth=-0.7, edge_width=0.5)],
+    "labelfree_256": [lf(nz=4, ny=256, nx=256, tilt_zenith=0.2, edge_width=0.5)],
 }
+COMPILED = (64, 128, 160, 192, 240, 256, 320, 384, 480, 512, 1024)
 
 
 def support_extent(mask):
@@ -47,7 +49,7 @@ def support_extent(mask):
 def test_support_contains_oracle_bank_and_fields(name):
     opts = CASES[name]
     o0 = opts[0]
-    fc, tc, nb = api.lateral_support(opts)
+    fc, tc, nb, (ly, lx) = api.lateral_support(opts, lengths=True)
     Xh = o0.nx // 2 + 1
     assert fc % 16 == 0 or fc == o0.nx
     assert tc % 16 == 0 or tc == Xh
@@ -63,6 +65,13 @@ def test_support_contains_oracle_bank_and_fields(name):
         pupil_x = max(pupil_x, px)
     # contains: every nonzero of the bank and of the pupil's columns is kept
     assert bank_x < tc and bank_y <= ky
+    # the synthesis' transforms hold the correlation without wrap-around, and the
+    # kept columns of the result as non-negative frequencies
+    assert 2 * bank_x + 1 <= lx <= o0.nx and 2 * bank_y + 1 <= ly <= o0.ny
+    assert 2 * (tc - 1) <= lx and fc <= lx
+    assert lx in COMPILED + (o0.nx,) and ly in COMPILED + (o0.ny,)
+    if o0.model not in (op.LABELFREE_3D, op.SECTORS9_3D):
+        assert (ly, lx) == (o0.ny, o0.nx)
     if fc < o0.nx:
         assert 2 * pupil_x + 1 <= fc
     # tight: at most one spare plus the rounding to 16 (the oracle's bank is a
@@ -75,5 +84,9 @@ def test_support_contains_oracle_bank_and_fields(name):
 
 def test_support_filling_the_grid_is_the_full_layout():
     o = lf(nx=16, ny=16, dy=0.15, dx=0.15)
-    fc, tc, nb = api.lateral_support([o])
-    assert (fc, tc, nb) == (16, 9, 16)
+    assert api.lateral_support([o], lengths=True) == (16, 9, 16, (16, 16))
+
+
+def test_bench_volume_runs_on_384_point_transforms():
+    o = lf(nz=96, ny=512, nx=512)
+    assert api.lateral_support([o], lengths=True) == (240, 176, 331, (384, 384))
