@@ -39,11 +39,11 @@ ETA_REL = 1e-3
 def kernel_bytes(name, Z, Y, X, sup, C=1, P=2):
     """Algorithmic HBM bytes one launch of each kernel must move in this step.
 
-    sup = (field columns, bank half-spectrum columns kt, band rows nb, (ly, lx))
-    of the lateral support (wo_lateral_support): the fields are kept on the
-    detection pupil's columns at ly points along y, the bank and the spectra on
-    the columns k < kt of every row (of the band rows once transformed along Y)."""
-    fc, kt, nb, (ly, _) = sup
+    sup: the lateral support (wo_lateral_support): the fields A and B are kept on
+    field_cols columns at ly points along y, the bank and the spectra on the
+    columns k < kt of every row (of the band rows once transformed along Y)."""
+    fa, fb = sup["field_cols"]
+    kt, nb, (ly, _) = sup["tf_cols"], sup["band_rows"], sup["tf_lengths"]
     Xh = X // 2 + 1
     cplx = 8
     full = Z * Y * X
@@ -58,8 +58,8 @@ def kernel_bytes(name, Z, Y, X, sup, C=1, P=2):
         "k_cols_y_inv": P * cplx * (band + rows_kt),
         "k_rows_c2r": P * (cplx * rows_kt + 4 * full),
         # transfer-function synthesis
-        "k_tf_fields_y": 2 * cplx * Z * ly * fc,
-        "k_tf_rows_lf": 2 * cplx * Z * ly * fc + 2 * cplx * tf_rows,
+        "k_tf_fields_y": cplx * Z * ly * (fa + fb),
+        "k_tf_rows_lf": cplx * Z * ly * (fa + fb) + 2 * cplx * tf_rows,
         "k_cols_y_tf": 2 * cplx * (tf_rows + band),
         # band rows' Z transform, plus the zeros of the rest of the bank
         "k_cols_expand": 2 * 2 * cplx * band + 2 * cplx * (Z * Y * Xh - band),
@@ -70,11 +70,14 @@ def kernel_bytes(name, Z, Y, X, sup, C=1, P=2):
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "labelfree3d_96x512x512_hbm_traffic.txt")
 CSRC = os.path.join(ROOT, "paper_2412_09775_amd", "csrc")
 # kernel name in the library's timing report -> symbol in the counter summary (the
-# column passes share one symbol across launches and are not listed)
-COUNTER_NAMES = {"k_zop<2>": "wo::k_zop<2, 1, 96>", "k_rows_r2c": "wo::k_rows_r2c<512>",
-                 "k_rows_c2r": "wo::k_rows_c2r<512>", "k_tf_rows_lf": "wo::k_tf_rows_lf<512>",
-                 "k_tf_fields_y": "wo::k_tf_fields_y<512, 2, false>",
-                 "k_cols_expand": "wo::k_cols_expand<96, 16>"}
+# column passes share one symbol across launches and are not listed); the TF
+# kernels are compiled for the synthesis' transform lengths (ly, lx)
+def counter_symbols(sup):
+    ly, lx = sup["tf_lengths"]
+    return {"k_zop<2>": "wo::k_zop<2, 1, 96>", "k_rows_r2c": "wo::k_rows_r2c<512>",
+            "k_rows_c2r": "wo::k_rows_c2r<512>", "k_tf_rows_lf": f"wo::k_tf_rows_lf<{lx}>",
+            "k_tf_fields_y": f"wo::k_tf_fields_y<{ly}, 2, false>",
+            "k_cols_expand": "wo::k_cols_expand<96, 16>"}
 
 
 def source_sha1():
@@ -88,17 +91,18 @@ def source_sha1():
     return h.hexdigest()
 
 
-def measured_traffic(kernel):
+def measured_traffic(kernel, sup):
     """HBM bytes per launch from the committed FETCH_SIZE/WRITE_SIZE summary, or None
     when the kernel sources changed since the counters were taken."""
+    names = counter_symbols(sup)
     try:
         lines = open(TRAFFIC_FILE).read().splitlines()
     except OSError:
         return None
     rec = [ln.split()[1] for ln in lines if ln.startswith("source_sha1")]
-    if not rec or rec[0] != source_sha1() or kernel not in COUNTER_NAMES:
+    if not rec or rec[0] != source_sha1() or kernel not in names:
         return None
-    want = COUNTER_NAMES[kernel]
+    want = names[kernel]
     best = None
     for ln in lines:
         f = ln.split("\t")
@@ -239,7 +243,7 @@ def main():
     o = api.Optics(**WORKLOAD)
     Z, Y, X = o.nz, o.ny, o.nx
     V = Z * Y * X
-    sup = api.lateral_support([o], lengths=True)
+    sup = api.lateral_support([o])
 
     # ---- inputs (untimed): specimen, forward model on the GPU, noise on the host
     t0 = time.time()
@@ -270,9 +274,14 @@ def main():
                                 api._ptr(ws_rec), ws_rec.numel(), sp)
         assert st == 0, st
 
+    ws_both = torch.empty(api.workspace_size([o], api.OP_TF_RECONSTRUCT), dtype=torch.uint8, device=dev)
+
     def full_step():
-        step_tf()
-        step_rec(tf_buf)
+        # TF synthesis and reconstruction in one call: the data's X and Y
+        # transforms run on the library's second stream beside the synthesis
+        st = lib.wo_transfer_function_reconstruct(arr, 1, api._ptr(tf_buf), api._ptr(d), None, eta,
+                                                  api._ptr(fout), api._ptr(ws_both), ws_both.numel(), sp)
+        assert st == 0, st
 
     for _ in range(args.warmup):
         full_step()
@@ -321,10 +330,13 @@ def main():
     print(f"[bench] fft schedules: {tuner}", file=sys.stderr, flush=True)
 
     # ---- per-kernel pass: K steps with every library kernel bracketed by HIP events
-    # (the events add gaps between launches, so this pass is not the timed one)
+    # (the events add gaps between launches, so this pass is not the timed one).
+    # The same kernels as two calls on one stream: each duration is the kernel's
+    # own, not stretched by kernels of the other stream running beside it.
     api.timing_enable(True)
     for _ in range(args.steps):
-        full_step()
+        step_tf()
+        step_rec(tf_buf)
     torch.cuda.synchronize()
     api.timing_enable(False)
     kern = api.timing_report()
@@ -353,6 +365,14 @@ def main():
         step_rec(tf_buf)
     torch.cuda.synchronize()
     ms_rec = (time.perf_counter() - r0) * 1e3 / args.steps
+    # the same step as two calls on one stream (no overlap), for comparison
+    torch.cuda.synchronize()
+    r0 = time.perf_counter()
+    for _ in range(args.steps):
+        step_tf()
+        step_rec(tf_buf)
+    torch.cuda.synchronize()
+    ms_two_calls = (time.perf_counter() - r0) * 1e3 / args.steps
 
     kernels = {}
     step_bytes = 0
@@ -369,7 +389,7 @@ def main():
     dom_ms = dom_rec[1] / dom_rec[0]
     ach = dom_b / (dom_ms * 1e-3) / 1e9
     roof = {"kernel": dom, "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": measured_traffic(dom),
+            "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": measured_traffic(dom, sup),
             "alg_bytes": dom_b}
 
     out = {
@@ -387,9 +407,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": "label-free 3D phase+absorption, 96x512x512, 1 channel x 2 properties",
                    "shape_zyx": [Z, Y, X], "voxel_um": [o.dz, o.dy, o.dx], "eta_rel": ETA_REL},
-        "lateral_support": {"field_cols": sup[0], "tf_cols": sup[1], "band_rows": sup[2],
-                            "tf_transform_yx": list(sup[3])},
+        "lateral_support": {k: list(v) if isinstance(v, tuple) else v for k, v in sup.items()},
         "reconstruct_cached_tf": {"ms": ms_rec, "voxels_per_s": V / (ms_rec * 1e-3)},
+        "ms_per_step_two_calls_one_stream": ms_two_calls,
         "fft_schedules": tuner,
         "roofline": roof,
         # every library kernel of the step: algorithmic bytes per step over the
@@ -799,8 +819,8 @@ def multi_aperture_section(api, torch, dev, steps, shape=(48, 512, 512)):
            "reconstruct_ms": (t2 - t1) * 1e3 / steps, "reconstruct_voxels_per_s": V * steps / (t2 - t1)}
     if zop:
         per = zop[1] / zop[0]
-        _, kt, nb = api.lateral_support([o])
-        b = 8 * Z * nb * kt * (9 + 9 + 1)
+        sp = api.lateral_support([o])
+        b = 8 * Z * sp["band_rows"] * sp["tf_cols"] * (9 + 9 + 1)
         res["k_zop<1>"] = {"avg_ms": round(per, 5), "alg_bytes": b, "alg_GBps": round(b / (per * 1e-3) / 1e9, 1)}
     print(f"[bench] multi-aperture: TF {res['tf_ms']:.2f} ms, reconstruct {res['reconstruct_ms']:.2f} ms",
           file=sys.stderr, flush=True)

@@ -87,7 +87,8 @@ enum {
   WO_OP_TRANSFER_FUNCTION = 0,
   WO_OP_FORWARD = 1,
   WO_OP_RECONSTRUCT = 2,
-  WO_OP_ADJOINT = 3
+  WO_OP_ADJOINT = 3,
+  WO_OP_TF_RECONSTRUCT = 4   /* wo_transfer_function_reconstruct */
 };
 
 /* Optics and sampling of one patch (Ext. Data Fig. 3: calc_ill_pupil takes
@@ -138,21 +139,24 @@ int wo_transfer_function(const wo_optics* o, int32_t n, void* tf_out, void* ws, 
 /* Lateral support of the model's fields and transfer-function bank for n
  * patches (Methods, pupils): the detection pupil is zero beyond NA_det/lambda0
  * and the source beyond its tilted disc of radius NA_ill/lambda0 (each widened
- * by the soft edge), so the label-free fields vanish outside the detection
- * pupil's columns, the bank outside the sum of the two supports (twice the
- * detection pupil's for fluorescence).  *field_cols: columns of the fields
- * kept by the transfer-function synthesis (nx: all); *tf_cols: the bank's
- * half-spectrum columns k < tf_cols that can be nonzero; *band_rows: its rows
- * y <= ky or y >= ny - ky, band_rows = 2 ky + 1 (ny: all rows).  Bounds keep one
- * spare column or row and are rounded up to multiples of 16.  tf_lengths[0..1]:
- * the (y, x) transform lengths of the synthesis -- the bank is a correlation
- * of the fields' spectra, so lengths beyond its extent give it exactly; the
- * label-free 3D models use the shortest compiled lengths that hold it, the
- * others (ny, nx).  The 3D linear calls (wo_forward, wo_reconstruct,
+ * by the soft edge), so the label-free field B = P g e^{..} vanishes outside
+ * the detection pupil's columns, A = S P e^{..} also outside the source's, and
+ * the bank outside the sum of the two supports (twice the detection pupil's
+ * for fluorescence).  Bounds keep one spare column or row and are rounded up
+ * to multiples of 16.  The 3D linear calls (wo_forward, wo_reconstruct,
  * wo_adjoint) read the bank only within the support and take it as zero
- * elsewhere, as wo_transfer_function writes it.  Outputs may be NULL. */
-int wo_lateral_support(const wo_optics* o, int32_t n, int32_t* field_cols, int32_t* tf_cols,
-                       int32_t* band_rows, int32_t* tf_lengths);
+ * elsewhere, as wo_transfer_function writes it. */
+typedef struct wo_support {
+  int32_t field_cols[2];  /* lateral columns the synthesis keeps of field A (or the
+                             fluorescence field) and of B (0: no second field) */
+  int32_t tf_cols;        /* the bank's half-spectrum columns k < tf_cols can be nonzero */
+  int32_t band_rows;      /* and its rows y <= ky or y >= ny - ky: 2 ky + 1 (ny: all) */
+  int32_t tf_lengths[2];  /* (y, x) transform lengths of the synthesis: the bank is a
+                             correlation of the fields' spectra, so lengths beyond its
+                             extent give it exactly; the label-free 3D models use the
+                             shortest compiled lengths that hold it, the others (ny, nx) */
+} wo_support;
+int wo_lateral_support(const wo_optics* o, int32_t n, wo_support* out);
 
 /* Forward model D_c = sum_p H_cp F_p + N b_c delta(nu), d_c = IFFT(D_c)
  * (Methods, "Linear contrast-separable shift-invariant imaging systems").
@@ -171,6 +175,17 @@ int wo_forward(const wo_optics* o, int32_t n, const void* tf, const float* f, co
  * is supported for P == 1 only (F = 0 where H = 0), else WO_EUNSUPPORTED. */
 int wo_reconstruct(const wo_optics* o, int32_t n, const void* tf, const float* d, const float* b,
                    double eta, float* f_out, void* ws, size_t ws_bytes, void* stream);
+
+/* Transfer-function synthesis followed by the Tikhonov reconstruction with
+ * that bank -- wo_transfer_function(o, n, tf_out, ...) then wo_reconstruct(o,
+ * n, tf_out, d, b, eta, f_out, ...), same arguments, results and errors -- in
+ * one call that overlaps the two: the data's X and Y transforms run on a
+ * second stream the library keeps per device (default priority), forked from
+ * and joined back into `stream` with events, beside the synthesis.  Workspace:
+ * wo_workspace_size(o, n, WO_OP_TF_RECONSTRUCT) bytes. */
+int wo_transfer_function_reconstruct(const wo_optics* o, int32_t n, void* tf_out, const float* d,
+                                     const float* b, double eta, float* f_out, void* ws,
+                                     size_t ws_bytes, void* stream);
 
 /* Adjoint g_p = IFFT(sum_c conj(H_cp) R_c): r [n][C][vol] -> g_out [n][P][vol]. */
 int wo_adjoint(const wo_optics* o, int32_t n, const void* tf, const float* r, float* g_out,

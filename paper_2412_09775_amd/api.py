@@ -29,6 +29,7 @@ OP_TRANSFER_FUNCTION = 0
 OP_FORWARD = 1
 OP_RECONSTRUCT = 2
 OP_ADJOINT = 3
+OP_TF_RECONSTRUCT = 4
 
 SYMBOLS = ("wo_bank_shape", "wo_workspace_size", "wo_transfer_function", "wo_forward",
            "wo_reconstruct", "wo_adjoint", "wo_strerror", "wo_version", "wo_timing_enable",
@@ -39,7 +40,7 @@ SYMBOLS = ("wo_bank_shape", "wo_workspace_size", "wo_transfer_function", "wo_for
            "wo_synth_thin_cells", "wo_add_gaussian_noise", "wo_crop_stacks", "wo_fft_tune",
            "wo_fft_plans_export", "wo_fft_plans_import", "wo_fft_plans_clear", "wo_fft_candidates",
            "wo_tile_grid", "wo_stitch_tiles", "wo_timing_select", "wo_midband_loss_grad_aberration",
-           "wo_lateral_support")
+           "wo_lateral_support", "wo_transfer_function_reconstruct")
 
 _FIELDS = ("model", "nz", "ny", "nx", "dz", "dy", "dx", "wavelength", "na_ill", "na_det",
            "n_medium", "defocus", "tilt_zenith", "tilt_azimuth", "edge_width", "swing")
@@ -87,6 +88,11 @@ class WoAutotuneOpts(ctypes.Structure):
                 ("lr_zernike", ctypes.c_double), ("zernike_bound", ctypes.c_double)]
 
 
+class WoSupport(ctypes.Structure):
+    _fields_ = [("field_cols", ctypes.c_int32 * 2), ("tf_cols", ctypes.c_int32),
+                ("band_rows", ctypes.c_int32), ("tf_lengths", ctypes.c_int32 * 2)]
+
+
 class WoError(RuntimeError):
     def __init__(self, status: int, where: str):
         msg = _lib.wo_strerror(status).decode() if _lib is not None else str(status)
@@ -111,12 +117,12 @@ def load(path: str = LIB_PATH):
                                   ctypes.POINTER(ctypes.c_int64)]
     lib.wo_workspace_size.argtypes = [op, i32, i32]
     lib.wo_workspace_size.restype = sz
-    lib.wo_lateral_support.argtypes = [op, i32, ctypes.POINTER(i32), ctypes.POINTER(i32),
-                                       ctypes.POINTER(i32), ctypes.POINTER(i32)]
+    lib.wo_lateral_support.argtypes = [op, i32, ctypes.POINTER(WoSupport)]
     lib.wo_transfer_function.argtypes = [op, i32, vp, vp, sz, vp]
     lib.wo_forward.argtypes = [op, i32, vp, vp, vp, vp, vp, sz, vp]
     lib.wo_reconstruct.argtypes = [op, i32, vp, vp, vp, ctypes.c_double, vp, vp, sz, vp]
     lib.wo_adjoint.argtypes = [op, i32, vp, vp, vp, vp, sz, vp]
+    lib.wo_transfer_function_reconstruct.argtypes = [op, i32, vp, vp, vp, ctypes.c_double, vp, vp, sz, vp]
     lib.wo_strerror.argtypes = [ctypes.c_int]
     lib.wo_strerror.restype = ctypes.c_char_p
     lib.wo_version.restype = ctypes.c_int
@@ -199,19 +205,15 @@ def bank_shape(optics):
     return C.value, P.value, dims.value, n.value
 
 
-def lateral_support(optics, lengths=False):
-    """(field columns, bank half-spectrum columns, band rows) of the model's lateral
-    support for these patches, plus the synthesis' (y, x) transform lengths when
-    `lengths` (wo_lateral_support)."""
+def lateral_support(optics):
+    """Lateral support of the model for these patches (wo_lateral_support) as a dict:
+    field_cols (A, B), tf_cols, band_rows, tf_lengths (y, x)."""
     lib = load()
     arr = optics_array(optics)
-    fc, tc, br = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
-    tl = (ctypes.c_int32 * 2)()
-    _check(lib.wo_lateral_support(arr, len(arr), ctypes.byref(fc), ctypes.byref(tc), ctypes.byref(br), tl),
-           "wo_lateral_support")
-    if lengths:
-        return fc.value, tc.value, br.value, (tl[0], tl[1])
-    return fc.value, tc.value, br.value
+    out = WoSupport()
+    _check(lib.wo_lateral_support(arr, len(arr), ctypes.byref(out)), "wo_lateral_support")
+    return {"field_cols": tuple(out.field_cols), "tf_cols": out.tf_cols, "band_rows": out.band_rows,
+            "tf_lengths": tuple(out.tf_lengths)}
 
 
 def workspace_size(optics, op: int) -> int:
@@ -297,6 +299,25 @@ def reconstruct(optics, tf, d, eta, b=None, ws=None, stream=None):
     lib = load()
     return _linear(lib.wo_reconstruct, "wo_reconstruct", optics, tf, d.contiguous(), fshape,
                    lambda out: (_ptr(b), ctypes.c_double(eta), _ptr(out)), ws, stream, OP_RECONSTRUCT)
+
+
+def transfer_function_reconstruct(optics, d, eta, b=None, tf=None, out=None, ws=None, stream=None):
+    """TF synthesis, then the Tikhonov reconstruction with it, overlapped in one call
+    (``wo_transfer_function_reconstruct``); returns (f, tf)."""
+    import torch
+    lib = load()
+    arr = optics_array(optics)
+    C, P, dims, _ = bank_shape(optics)
+    d = d.contiguous()
+    if tf is None:
+        tf = torch.empty(bank_dims(optics), dtype=torch.complex64, device=d.device)
+    if out is None:
+        out = torch.empty((len(arr), P) + _vol(optics), dtype=torch.float32, device=d.device)
+    ws, _ = _workspace(optics, OP_TF_RECONSTRUCT, d.device, ws)
+    _check(lib.wo_transfer_function_reconstruct(arr, len(arr), _ptr(tf), _ptr(d), _ptr(b), ctypes.c_double(eta),
+                                                _ptr(out), _ptr(ws), ws.numel(), _stream(stream)),
+           "wo_transfer_function_reconstruct")
+    return out, tf
 
 
 def adjoint(optics, tf, r, ws=None, stream=None):

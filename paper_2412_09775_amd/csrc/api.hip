@@ -320,6 +320,13 @@ LatSupport lateral_support(const wo_optics* o, int32_t n) {
     ls.xc = xc;
     ls.kp = px;
   }
+  ls.xa = ls.xc;
+  ls.kpa = ls.kp;
+  const int xa = (2 * ax + 1 + 15) / 16 * 16;
+  if (o->model != WO_MODEL_FLUOR_3D && xa < ls.xc && ax <= ls.kp && xa - ax <= ls.xc - ls.kp) {
+    ls.xa = xa;   // A's columns: a subset of B's
+    ls.kpa = ax;
+  }
   const int kt = (px + ax + 1 + 15) / 16 * 16;
   if (kt < Xh) ls.kt = kt;
   if (2 * (py + ay) + 1 < Y) ls.ky = py + ay;
@@ -340,7 +347,7 @@ LatSupport lateral_support(const wo_optics* o, int32_t n) {
 
 // Complex values of the compact fields of nv field sets, rounded up to 256 bytes.
 long compact_fields_elems(int nv, int nf, const Shape& s, const LatSupport& sup) {
-  return ((long)nv * nf * s.Z * sup.ly * sup.xc + 31) / 32 * 32;
+  return ((long)nv * s.Z * sup.ly * (nf == 2 ? sup.xa + sup.xc : sup.xc) + 31) / 32 * 32;
 }
 
 // The support the transfer-function synthesis works on.  The label-free 3D
@@ -387,45 +394,101 @@ size_t linear_ws(int32_t n, const Shape& s) {
     if (_e != hipSuccess) return WO_EHIP;    \
   } while (0)
 
-// The FFT / operator / inverse-FFT sequence shared by forward, reconstruct and adjoint.
-int run_linear(const wo_optics* o, int32_t n, const Shape& s, const float2* tf, const float* in,
-               float* out, const float* bg, int mode, float eta, void* ws, hipStream_t st) {
-  const int cin = mode == kModeForward ? s.P : s.C;
-  const int cout = mode == kModeForward ? s.C : s.P;
-  const int CH = cin > cout ? cin : cout;
-  const long zd = s.thin ? 1 : s.Z;
+// The FFT / operator / inverse-FFT sequence shared by forward, reconstruct and
+// adjoint, in two halves: linear_in transforms the input into the spectrum
+// (along X and Y), linear_out applies the per-frequency operator with the Z
+// transforms and transforms back.  The bank vanishes outside the transfer
+// function's lateral support, and so do the forward model's spectrum (but for
+// its DC background term), the Tikhonov solution and the adjoint: for the 3D
+// models the spectra are kept as the columns k < kt of every row (stored for
+// the band rows only) and the Z pass covers the band.
+struct LinearPlan {
+  int cin, cout, CH;
+  long zd;
+  bool banded;
+  int kt, ky;
+};
+
+LinearPlan linear_plan(const wo_optics* o, int32_t n, const Shape& s, int mode) {
+  LinearPlan p;
+  p.cin = mode == kModeForward ? s.P : s.C;
+  p.cout = mode == kModeForward ? s.C : s.P;
+  p.CH = p.cin > p.cout ? p.cin : p.cout;
+  p.zd = s.thin ? 1 : s.Z;
+  const LatSupport sup = s.thin ? full_support(sampling_of(o)) : lateral_support(o, n);
+  p.banded = !s.thin && (sup.kt < s.Xh || sup.ky < s.Y);
+  p.kt = p.banded ? sup.kt : (int)s.Xh;
+  p.ky = p.banded ? sup.ky : (int)s.Y;
+  return p;
+}
+
+int linear_in(const wo_optics* o, int32_t n, const Shape& s, const float* in, int mode, void* ws,
+              hipStream_t st) {
+  const LinearPlan p = linear_plan(o, n, s, mode);
+  float2* spec = (float2*)ws;
+  RowGroups gin{p.cin * p.zd * s.Y, p.cin * p.zd * s.Y, p.CH * p.zd * s.Y, n};
+  if (p.banded) {
+    WO_TRY(launch_rows_r2c(in, spec, (int)s.X, gin, st, p.kt, p.kt));
+    WO_TRY(launch_cols(spec, (int)s.Y, p.kt, p.cin * p.zd, p.CH * p.zd, n, -1.f, st, "k_cols_y_fwd", 1,
+                       p.ky));
+  } else {
+    WO_TRY(launch_rows_r2c(in, spec, (int)s.X, gin, st));
+    WO_TRY(launch_cols(spec, (int)s.Y, s.Xh, p.cin * p.zd, p.CH * p.zd, n, -1.f, st, "k_cols_y_fwd"));
+  }
+  return WO_OK;
+}
+
+int linear_out(const wo_optics* o, int32_t n, const Shape& s, const float2* tf, float* out,
+               const float* bg, int mode, float eta, void* ws, hipStream_t st) {
+  const LinearPlan p = linear_plan(o, n, s, mode);
   float2* spec = (float2*)ws;
   const long M = s.Y * s.Xh;
   const double nfull = s.thin ? (double)s.Y * s.X : (double)s.Z * s.Y * s.X;
   const float inv_n = (float)(1.0 / nfull);
-  RowGroups gin{cin * zd * s.Y, cin * zd * s.Y, CH * zd * s.Y, n};
-  RowGroups gout{cout * zd * s.Y, CH * zd * s.Y, cout * zd * s.Y, n};
-  const LatSupport sup = s.thin ? full_support(sampling_of(o)) : lateral_support(o, n);
-  if (!s.thin && (sup.kt < s.Xh || sup.ky < s.Y)) {
-    // The bank vanishes outside the transfer function's lateral support, and
-    // so do the forward model's spectrum (but for its DC background term), the
-    // Tikhonov solution and the adjoint: the spectra are kept as the columns
-    // k < kt of every row (stored for the band rows only) and the Z pass
-    // covers the band.
-    const int kt = sup.kt, ky = sup.ky;
-    const SpecBand band{(int)s.Y, kt, ky};
-    WO_TRY(launch_rows_r2c(in, spec, (int)s.X, gin, st, kt, kt));
-    WO_TRY(launch_cols(spec, (int)s.Y, kt, cin * zd, CH * zd, n, -1.f, st, "k_cols_y_fwd", 1, ky));
-    WO_TRY(launch_zop(spec, tf, s.C, s.P, (int)s.Z, M, CH, n, mode, eta, bg, inv_n, nfull, st, &band));
-    WO_TRY(launch_cols(spec, (int)s.Y, kt, cout * zd, CH * zd, n, 1.f, st, "k_cols_y_inv", 2, ky));
-    WO_TRY(launch_rows_c2r(spec, out, (int)s.X, gout, 1.f, st, kt, kt));
+  RowGroups gout{p.cout * p.zd * s.Y, p.CH * p.zd * s.Y, p.cout * p.zd * s.Y, n};
+  if (p.banded) {
+    const SpecBand band{(int)s.Y, p.kt, p.ky};
+    WO_TRY(launch_zop(spec, tf, s.C, s.P, (int)s.Z, M, p.CH, n, mode, eta, bg, inv_n, nfull, st, &band));
+    WO_TRY(launch_cols(spec, (int)s.Y, p.kt, p.cout * p.zd, p.CH * p.zd, n, 1.f, st, "k_cols_y_inv", 2,
+                       p.ky));
+    WO_TRY(launch_rows_c2r(spec, out, (int)s.X, gout, 1.f, st, p.kt, p.kt));
     return WO_OK;
   }
-  WO_TRY(launch_rows_r2c(in, spec, (int)s.X, gin, st));
-  WO_TRY(launch_cols(spec, (int)s.Y, s.Xh, cin * zd, CH * zd, n, -1.f, st, "k_cols_y_fwd"));
   if (s.thin) {
-    WO_TRY(launch_op2d(spec, tf, s.C, s.P, M, CH, n, mode, eta, bg, inv_n, nfull, st));
+    WO_TRY(launch_op2d(spec, tf, s.C, s.P, M, p.CH, n, mode, eta, bg, inv_n, nfull, st));
   } else {
-    WO_TRY(launch_zop(spec, tf, s.C, s.P, (int)s.Z, M, CH, n, mode, eta, bg, inv_n, nfull, st));
+    WO_TRY(launch_zop(spec, tf, s.C, s.P, (int)s.Z, M, p.CH, n, mode, eta, bg, inv_n, nfull, st));
   }
-  WO_TRY(launch_cols(spec, (int)s.Y, s.Xh, cout * zd, CH * zd, n, 1.f, st, "k_cols_y_inv"));
+  WO_TRY(launch_cols(spec, (int)s.Y, s.Xh, p.cout * p.zd, p.CH * p.zd, n, 1.f, st, "k_cols_y_inv"));
   WO_TRY(launch_rows_c2r(spec, out, (int)s.X, gout, 1.f, st));
   return WO_OK;
+}
+
+int run_linear(const wo_optics* o, int32_t n, const Shape& s, const float2* tf, const float* in,
+               float* out, const float* bg, int mode, float eta, void* ws, hipStream_t st) {
+  int r = linear_in(o, n, s, in, mode, ws, st);
+  if (r) return r;
+  return linear_out(o, n, s, tf, out, bg, mode, eta, ws, st);
+}
+
+// A second stream per device (default priority, created on first use, kept
+// for the life of the process) for work a call runs beside its own stream.
+hipError_t side_stream(hipStream_t* out) {
+  static std::mutex mu;
+  static std::map<int, hipStream_t> streams;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = streams.find(dev);
+  if (it == streams.end()) {
+    hipStream_t st;
+    e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+    if (e != hipSuccess) return e;
+    it = streams.emplace(dev, st).first;
+  }
+  *out = it->second;
+  return hipSuccess;
 }
 
 
@@ -1042,39 +1105,33 @@ size_t wo_workspace_size(const wo_optics* o, int32_t n, int32_t op) {
   Shape s;
   if (!o || n < 1 || !bank_shape(o, &s)) return 0;
   if (op == WO_OP_TRANSFER_FUNCTION) return tf_ws(o, n, s);
+  if (op == WO_OP_TF_RECONSTRUCT) return tf_ws(o, n, s) + linear_ws(n, s);
   if (op == WO_OP_FORWARD || op == WO_OP_RECONSTRUCT || op == WO_OP_ADJOINT) return linear_ws(n, s);
   return 0;
 }
 
-int wo_lateral_support(const wo_optics* o, int32_t n, int32_t* field_cols, int32_t* tf_cols,
-                       int32_t* band_rows, int32_t* tf_lengths) {
+int wo_lateral_support(const wo_optics* o, int32_t n, wo_support* out) {
   int st = validate(o, n);
   if (st) return st;
+  if (!out) return WO_EINVAL;
   Shape s;
   if (!bank_shape(o, &s)) return WO_EINVAL;
   const LatSupport ls = lateral_support(o, n);
   bool compact_out = false;
   const LatSupport ts = tf_support(o, n, s, &compact_out);
-  const int nb = ls.ky >= o->ny ? o->ny : 2 * ls.ky + 1;
-  if (field_cols) *field_cols = ts.xc;
-  if (tf_cols) *tf_cols = ls.kt;
-  if (band_rows) *band_rows = nb;
-  if (tf_lengths) {
-    tf_lengths[0] = ts.ly;
-    tf_lengths[1] = ts.lx;
-  }
+  const bool one_field = o->model == WO_MODEL_FLUOR_3D;
+  out->field_cols[0] = one_field ? ts.xc : ts.xa;
+  out->field_cols[1] = one_field ? 0 : ts.xc;
+  out->tf_cols = ls.kt;
+  out->band_rows = ls.ky >= o->ny ? o->ny : 2 * ls.ky + 1;
+  out->tf_lengths[0] = ts.ly;
+  out->tf_lengths[1] = ts.lx;
   return WO_OK;
 }
 
-int wo_transfer_function(const wo_optics* o, int32_t n, void* tf_out, void* ws, size_t ws_bytes,
-                         void* stream) {
-  int st = validate(o, n);
-  if (st) return st;
-  if (!tf_out || !ws) return WO_EINVAL;
-  Shape s;
-  bank_shape(o, &s);
-  if (ws_bytes < tf_ws(o, n, s)) return WO_ENOMEM;
-  hipStream_t hs = (hipStream_t)stream;
+// Transfer-function synthesis of validated optics into tf_out (workspace
+// tf_ws bytes at ws).
+static int run_tf(const wo_optics* o, int32_t n, const Shape& s, void* tf_out, void* ws, hipStream_t hs) {
   const int fs = field_sets(o);
   const int nv = n * fs;          // field sets: patch i, aperture c at i * fs + c
   std::vector<DevOptics> h(nv);
@@ -1164,6 +1221,17 @@ int wo_transfer_function(const wo_optics* o, int32_t n, void* tf_out, void* ws, 
   return WO_OK;
 }
 
+int wo_transfer_function(const wo_optics* o, int32_t n, void* tf_out, void* ws, size_t ws_bytes,
+                         void* stream) {
+  int st = validate(o, n);
+  if (st) return st;
+  if (!tf_out || !ws) return WO_EINVAL;
+  Shape s;
+  bank_shape(o, &s);
+  if (ws_bytes < tf_ws(o, n, s)) return WO_ENOMEM;
+  return run_tf(o, n, s, tf_out, ws, (hipStream_t)stream);
+}
+
 int wo_forward(const wo_optics* o, int32_t n, const void* tf, const float* f, const float* b,
                float* d_out, void* ws, size_t ws_bytes, void* stream) {
   if (!o || n < 1) return WO_EINVAL;
@@ -1198,6 +1266,43 @@ int wo_reconstruct(const wo_optics* o, int32_t n, const void* tf, const float* d
   if (ws_bytes < linear_ws(n, s)) return WO_ENOMEM;
   return run_linear(o, n, s, (const float2*)tf, d, f_out, b, kModeSolve, (float)eta, ws,
                     (hipStream_t)stream);
+}
+
+int wo_transfer_function_reconstruct(const wo_optics* o, int32_t n, void* tf_out, const float* d,
+                                     const float* b, double eta, float* f_out, void* ws,
+                                     size_t ws_bytes, void* stream) {
+  int st = validate(o, n);
+  if (st) return st;
+  if (!tf_out || !d || !f_out || !ws) return WO_EINVAL;
+  if (!(eta >= 0.0) || !isfinite(eta)) return WO_EINVAL;
+  Shape s;
+  bank_shape(o, &s);
+  if (s.P != 1 && s.P != 2 && s.P != 4) return WO_EUNSUPPORTED;
+  if (!s.thin && !zop_fits((int)s.Z, std::max(s.C, s.P))) return WO_EUNSUPPORTED;
+  if (eta == 0.0 && s.P != 1) return WO_EUNSUPPORTED;
+  const size_t wt = tf_ws(o, n, s);
+  if (ws_bytes < wt + linear_ws(n, s)) return WO_ENOMEM;
+  void* wl = (char*)ws + wt;
+  hipStream_t hs = (hipStream_t)stream, side;
+  if (side_stream(&side) != hipSuccess) return WO_EHIP;
+  // fork: the data's X and Y transforms on the side stream, after the work
+  // already queued on the caller's stream; join before the Z pass
+  hipEvent_t fork, join;
+  if (hipEventCreateWithFlags(&fork, hipEventDisableTiming) != hipSuccess) return WO_EHIP;
+  if (hipEventCreateWithFlags(&join, hipEventDisableTiming) != hipSuccess) {
+    (void)hipEventDestroy(fork);
+    return WO_EHIP;
+  }
+  int r = WO_OK;
+  if (hipEventRecord(fork, hs) != hipSuccess || hipStreamWaitEvent(side, fork, 0) != hipSuccess) r = WO_EHIP;
+  if (!r) r = linear_in(o, n, s, d, kModeSolve, wl, side);
+  if (!r && hipEventRecord(join, side) != hipSuccess) r = WO_EHIP;
+  if (!r) r = run_tf(o, n, s, tf_out, ws, hs);
+  if (!r && hipStreamWaitEvent(hs, join, 0) != hipSuccess) r = WO_EHIP;
+  if (!r) r = linear_out(o, n, s, (const float2*)tf_out, f_out, b, kModeSolve, (float)eta, wl, hs);
+  (void)hipEventDestroy(fork);
+  (void)hipEventDestroy(join);
+  return r;
 }
 
 int wo_adjoint(const wo_optics* o, int32_t n, const void* tf, const float* r, float* g_out,

@@ -158,14 +158,18 @@ hipError_t launch_set_params(DevOptics* dst, const DevOptics* host, int n, hipSt
 // A and B, so a transform of ly x lx points (at least the correlation's
 // extent) yields it exactly: the field kernel's inverse Y transform has ly
 // points, the row kernel's X transforms lx (ly = ny, lx = nx: the grid's own).
+// The label-free field A = S P e^{..} vanishes outside the source's support
+// too: it is kept on its own xa compact columns (last non-negative column
+// kpa), a subset of B's xc columns (xa = xc: the same layout).
 struct LatSupport {
   int xc, kp;
   int kt;
   int ky;
   int ly, lx;
+  int xa, kpa;
 };
 inline LatSupport full_support(const Sampling& sm) {
-  return LatSupport{sm.nx, sm.nx - 1, sm.nx / 2 + 1, sm.ny, sm.ny, sm.nx};
+  return LatSupport{sm.nx, sm.nx - 1, sm.nx / 2 + 1, sm.ny, sm.ny, sm.nx, sm.nx, sm.nx - 1};
 }
 // Column tile width of the field kernel for a transform of ly points (0: ny);
 // the pupil-sum partials hold ceil(xc / width) doubles per patch.

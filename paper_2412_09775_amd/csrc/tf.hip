@@ -79,10 +79,11 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
 
 // ------------------------------------------------------------------ fields, inverse Y
 
-// ab layout: [patch][field][z][y][c] complex (field 0 = A or the fluorescence
-// field, field 1 = B), c the compact column of the lateral frequency kx (see
-// field_column; c = kx when XC = X), y one of the LY points of the inverse Y
-// transform.  LY = Y is the grid's own transform; a shorter LY (still longer
+// ab layout per patch: field 0 (A, or the fluorescence field) [z][y][ca],
+// then field 1 (B) [z][y][c]: c the compact column of the lateral frequency kx
+// among B's XC kept columns (see field_column; c = kx when XC = X), ca among
+// A's XA (last non-negative column KPA; XA = XC: the same columns), y one of
+// the LY points of the inverse Y transform.  LY = Y is the grid's own transform; a shorter LY (still longer
 // than twice the support's extent along y) samples the same band-limited
 // fields more coarsely: frequency index i of the LY-point transform stands for
 // the grid's frequency (i or i - LY) / (Y dy).  A workgroup owns one column tile of one patch and a
@@ -96,11 +97,19 @@ __global__ __launch_bounds__(1024) void k_tf_fields_y(const DevOptics* __restric
                                                       Sampling sm, float2* __restrict__ ab,
                                                       double* __restrict__ partials, int W,
                                                       long tiles_x, int ZC, int XC, int KP, int LY,
-                                                      FftPlan plan) {
+                                                      int XA, int KPA, FftPlan plan) {
   __shared__ double red[kMaxThreads / 64];
   extern __shared__ float2 smem[];
   const int Y = NS > 0 ? NS : LY;   // transform length
   const int X = sm.nx, Z = sm.nz;
+  // field f of this patch at plane z, row y, compact column c of B's layout;
+  // nullptr where A keeps no column
+  auto field_at = [&](long patch, int f, int z, int y, int c) -> float2* {
+    float2* pa = ab + patch * (long)Z * Y * (NF == 2 ? XA + XC : XC);
+    if (NF == 1 || f == 1) return pa + (NF == 2 ? (long)Z * Y * XA : 0) + ((long)z * Y + y) * XC + c;
+    const int ca = XA == XC ? c : compact_column(field_column(c, KP, X, XC), KPA, X, XA);
+    return ca < 0 ? nullptr : pa + ((long)z * Y + y) * XA + ca;
+  };
   // frequency of transform index i: the grid's spacing 1 / (ny dy), wrapped at Y
   auto freq_y = [&](int i) { return (double)(i < (Y + 1) / 2 ? i : i - Y) / ((double)sm.ny * sm.dy); };
   float2* tw = smem;
@@ -232,10 +241,11 @@ __global__ __launch_bounds__(1024) void k_tf_fields_y(const DevOptics* __restric
           }
           dft_small<RL>(v, 1.f);
           const int f = l >> wsh, c = x0 + (l & (W - 1));
-          if (c < XC) {
-            float2* dst = ab + ((patch * nf + f) * Z + z) * (long)Y * XC + c;
+          float2* dst = c < XC ? field_at(patch, f, z, 0, c) : nullptr;
+          if (dst) {
+            const int pitch = (NF == 2 && f == 0) ? XA : XC;
 #pragma unroll
-            for (int r = 0; r < RL; ++r) dst[(long)(k + r * NSL) * XC] = v[r];
+            for (int r = 0; r < RL; ++r) dst[(long)(k + r * NSL) * pitch] = v[r];
           }
         }
       }
@@ -322,7 +332,8 @@ __global__ __launch_bounds__(1024) void k_tf_fields_y(const DevOptics* __restric
         const int r = e & (nf * W - 1);
         const int f = r >> wsh, w = r & (W - 1);
         const int c = x0 + w;
-        if (c < XC) ab[(((patch * nf + f) * Z + z) * (long)Y + ky) * XC + c] = v;
+        float2* dst = c < XC ? field_at(patch, f, z, ky, c) : nullptr;
+        if (dst) *dst = v;
       });
       __syncthreads();
     }
@@ -357,9 +368,13 @@ int tf_tile_width(const Sampling& sm, int ly) {
 hipError_t launch_tf_fields_y(const DevOptics* opt, const Sampling& sm, int npatch, float2* ab,
                               double* partials, hipStream_t s, const LatSupport* sup) {
   const LatSupport ls = sup ? *sup : full_support(sm);
-  if (ls.xc < 1 || ls.xc > sm.nx || ls.kp < 0 || ls.kp >= ls.xc || ls.ly < 2 || ls.ly > sm.ny)
+  if (ls.xc < 1 || ls.xc > sm.nx || ls.kp < 0 || ls.kp >= ls.xc || ls.ly < 2 || ls.ly > sm.ny ||
+      ls.xa < 1 || ls.xa > ls.xc || ls.kpa < 0 || ls.kpa > ls.kp ||
+      ls.xa - ls.kpa > ls.xc - ls.kp)   // A's columns among B's
     return hipErrorInvalidValue;
   const int LY = ls.ly;
+  const bool one_field = sm.model == kFluor3D;
+  const int xa = one_field ? ls.xc : ls.xa, kpa = one_field ? ls.kp : ls.kpa;
   FftPlan plan;
   if (!make_plan(LY, &plan)) return hipErrorInvalidValue;
   const int nf = sm.model == kFluor3D ? 1 : 2;
@@ -376,7 +391,7 @@ hipError_t launch_tf_fields_y(const DevOptics* opt, const Sampling& sm, int npat
   ScopedTiming _t("k_tf_fields_y", s);
 #define WO_FIELDS(NN, FF, AA)                                                                    \
   hipLaunchKernelGGL((k_tf_fields_y<NN, FF, AA>), dim3((unsigned)nwg), dim3(thr), lds, s, opt, sm, ab, \
-                     partials, W, tiles, ZC, ls.xc, ls.kp, LY, plan)
+                     partials, W, tiles, ZC, ls.xc, ls.kp, LY, xa, kpa, plan)
 #define X_(NN)                                                                                   \
   case NN:                                                                                       \
     if (nf == 2) {                                                                               \
@@ -415,7 +430,8 @@ __global__ __launch_bounds__(1024) void k_tf_rows_lf(const double* __restrict__ 
                                                      float2* __restrict__ out, long patch_stride,
                                                      long pstride, long zstride, int rows_per_wg,
                                                      long wg_per_patch, int XC, int KP, int KT,
-                                                     int OP, int LY, int LX, FftPlan plan) {
+                                                     int OP, int LY, int LX, int XA, int KPA,
+                                                     FftPlan plan) {
   __shared__ double ibg_s;
   extern __shared__ float2 smem[];
   // transform lengths: LY rows per plane (the field kernel's), X = LX points
@@ -431,19 +447,25 @@ __global__ __launch_bounds__(1024) void k_tf_rows_lf(const double* __restrict__ 
   const long row0 = (blockIdx.x - patch * wg_per_patch) * (long)rows_per_wg;
   const int nr = (int)min((long)rows_per_wg, rpp - row0);
   const int z0 = (int)(row0 / Y), y0 = (int)(row0 - (long)z0 * Y);
-  const float2* a_src = ab + (patch * 2 + 0) * rpp * XC;
-  const float2* b_src = ab + (patch * 2 + 1) * rpp * XC;
+  const float2* a_src = ab + patch * rpp * (XA + XC);
+  const float2* b_src = a_src + rpp * XA;
   const int PS = pad_shift(X);   // row padding
   const int LS = row_stride(X);      // padded line pitch in LDS
-  const int neg0 = X - (XC - KP - 1);   // first stored negative-frequency column
-  // line 2r holds a, line 2r + 1 holds b of row r.  A column the field kernel
-  // does not store loads column KP (a valid address, no branch, so the loads
+  // line 2r holds a (XA columns, last non-negative KPA), line 2r + 1 holds b
+  // (XC, KP) of row r.  A column the field kernel does not store loads the
+  // line's last non-negative column (a valid address, no branch, so the loads
   // of a thread stay in flight together) and is zeroed after the loads.
   auto load = [&](int t, int i) {
-    const float2* src = ((t & 1) ? b_src : a_src) + (row0 + (t >> 1)) * XC;
-    return src[i <= KP ? i : max(i - (X - XC), KP)];
+    const bool isb = t & 1;
+    const int xc = isb ? XC : XA, kp = isb ? KP : KPA;
+    const float2* src = (isb ? b_src : a_src) + (row0 + (t >> 1)) * xc;
+    return src[i <= kp ? i : max(i - (X - xc), kp)];
   };
-  auto kept = [&](int t, int i, float2 v) { return (i <= KP || i >= neg0) ? v : make_float2(0.f, 0.f); };
+  auto kept = [&](int t, int i, float2 v) {
+    const bool isb = t & 1;
+    const int xc = isb ? XC : XA, kp = isb ? KP : KPA;
+    return (i <= kp || i >= X - (xc - kp - 1)) ? v : make_float2(0.f, 0.f);
+  };
   if constexpr (NS > 0) {
     // Inverse transforms of a and b in reversed radix order, the first pass
     // straight from memory; their last pass, the product c = b conj(a) /
@@ -565,7 +587,8 @@ hipError_t launch_tf_rows_labelfree(const double* partials, const Sampling& sm, 
   const LatSupport ls = sup ? *sup : full_support(sm);
   const int LX = ls.lx, LY = ls.ly;
   if (ls.xc < 1 || ls.xc > LX || ls.kp < 0 || ls.kp >= ls.xc || ls.kt < 1 || 2 * (ls.kt - 1) > LX ||
-      LX > sm.nx || LY < 2 || LY > sm.ny)
+      LX > sm.nx || LY < 2 || LY > sm.ny || ls.xa < 1 || ls.xa > ls.xc || ls.kpa < 0 ||
+      ls.kpa > ls.kp || ls.xa - ls.kpa > ls.xc - ls.kp)
     return hipErrorInvalidValue;
   const int OP = pitch > 0 ? pitch : sm.nx / 2 + 1;
   if (OP < ls.kt) return hipErrorInvalidValue;
@@ -591,7 +614,7 @@ hipError_t launch_tf_rows_labelfree(const double* partials, const Sampling& sm, 
   case NN:                                                                                       \
     hipLaunchKernelGGL((k_tf_rows_lf<NN>), dim3((unsigned)nwg), dim3(thr), lds, s, partials, tiles_x, \
                        sm, ab, out, patch_stride, pstride, zstride, R, wpp, ls.xc, ls.kp, ls.kt, OP, \
-                       LY, LX, plan);                                                            \
+                       LY, LX, ls.xa, ls.kpa, plan);                                             \
     return hipGetLastError();
   if (c.plan == 0) switch (LX) {
       WO_LATERAL_SIZES(X_)
@@ -601,7 +624,7 @@ hipError_t launch_tf_rows_labelfree(const double* partials, const Sampling& sm, 
 #undef X_
   hipLaunchKernelGGL((k_tf_rows_lf<0>), dim3((unsigned)nwg), dim3(thr), lds, s, partials, tiles_x, sm,
                      ab, out, patch_stride, pstride, zstride, R, wpp, ls.xc, ls.kp, ls.kt, OP, LY, LX,
-                     plan);
+                     ls.xa, ls.kpa, plan);
   return hipGetLastError();
 }
 

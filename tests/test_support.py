@@ -49,20 +49,28 @@ def support_extent(mask):
 def test_support_contains_oracle_bank_and_fields(name):
     opts = CASES[name]
     o0 = opts[0]
-    fc, tc, nb, (ly, lx) = api.lateral_support(opts, lengths=True)
+    sup = api.lateral_support(opts)
+    (fa, fc), tc, nb, (ly, lx) = sup["field_cols"], sup["tf_cols"], sup["band_rows"], sup["tf_lengths"]
+    if o0.model == op.FLUOR_3D:
+        assert fc == 0
+        fc = fa
     Xh = o0.nx // 2 + 1
     assert fc % 16 == 0 or fc == o0.nx
     assert tc % 16 == 0 or tc == Xh
     assert nb % 2 == 1 or nb == o0.ny
     ky = (nb - 1) // 2 if nb < o0.ny else o0.ny
-    bank_y = bank_x = pupil_x = 0
+    bank_y = bank_x = pupil_x = source_x = 0
     for o in opts:
         bank = tfm.transfer_function(o)
         mag = np.abs(bank).max(axis=tuple(range(bank.ndim - 2)))
         my, mx = support_extent(mag > 1e-9 * mag.max())
         bank_y, bank_x = max(bank_y, my), max(bank_x, mx)
-        _, px = support_extent(np.abs(op.detection_pupil(o)) > 0)
+        P = np.abs(op.detection_pupil(o)) > 0
+        _, px = support_extent(P)
         pupil_x = max(pupil_x, px)
+        if o.model != op.FLUOR_3D:
+            _, sx = support_extent(P & (np.abs(op.illumination_pupil(o)) > 0))
+            source_x = max(source_x, sx)
     # contains: every nonzero of the bank and of the pupil's columns is kept
     assert bank_x < tc and bank_y <= ky
     # the synthesis' transforms hold the correlation without wrap-around, and the
@@ -80,13 +88,19 @@ def test_support_contains_oracle_bank_and_fields(name):
     assert nb == o0.ny or ky - bank_y <= 3
     if fc < o0.nx:
         assert fc - (2 * pupil_x + 1) < 16 + 2
+    # field A keeps the source's columns (within B's), tightly when narrower
+    if o0.model != op.FLUOR_3D:
+        assert 2 * source_x + 1 <= fa <= fc
+        assert fa == fc or fa - (2 * source_x + 1) < 16 + 2
 
 
 def test_support_filling_the_grid_is_the_full_layout():
     o = lf(nx=16, ny=16, dy=0.15, dx=0.15)
-    assert api.lateral_support([o], lengths=True) == (16, 9, 16, (16, 16))
+    assert api.lateral_support([o]) == {"field_cols": (16, 16), "tf_cols": 9, "band_rows": 16,
+                                        "tf_lengths": (16, 16)}
 
 
 def test_bench_volume_runs_on_384_point_transforms():
     o = lf(nz=96, ny=512, nx=512)
-    assert api.lateral_support([o], lengths=True) == (240, 176, 331, (384, 384))
+    assert api.lateral_support([o]) == {"field_cols": (112, 240), "tf_cols": 176, "band_rows": 331,
+                                        "tf_lengths": (384, 384)}
