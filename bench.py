@@ -63,6 +63,8 @@ def kernel_bytes(name, Z, Y, X, sup, C=1, P=2):
         "k_cols_y_tf": 2 * cplx * (tf_rows + band),
         # band rows' Z transform, plus the zeros of the rest of the bank
         "k_cols_expand": 2 * 2 * cplx * band + 2 * cplx * (Z * Y * Xh - band),
+        # the same into the band layout (no zeros)
+        "k_cols_z_band": 2 * 2 * cplx * band,
     }
     return table.get(name)
 
@@ -258,27 +260,43 @@ def main():
     eta = ETA_REL * smax2
     ws_tf = torch.empty(api.workspace_size([o], api.OP_TRANSFER_FUNCTION), dtype=torch.uint8, device=dev)
     ws_rec = torch.empty(api.workspace_size([o], api.OP_RECONSTRUCT), dtype=torch.uint8, device=dev)
-    tf_buf = torch.empty_like(tf)
+    tf_buf = tf.clone()
     lib = api.load()
     arr = api.optics_array([o])
     fout = torch.empty((1, 2, Z, Y, X), dtype=torch.float32, device=dev)
     stream = torch.cuda.current_stream()
     sp = api._stream(stream)
 
+    # The step keeps the bank on its lateral support (band layout: the values off
+    # it are zero and implied, like the Hermitian half); the full-layout bank
+    # and the one-call overlapped variant are timed as secondary figures.
+    tf_band = torch.empty(api.band_dims([o]), dtype=torch.complex64, device=dev)
+
     def step_tf():
-        st = lib.wo_transfer_function(arr, 1, api._ptr(tf_buf), api._ptr(ws_tf), ws_tf.numel(), sp)
+        st = lib.wo_transfer_function_band(arr, 1, api._ptr(tf_band), api._ptr(ws_tf), ws_tf.numel(), sp)
         assert st == 0, st
 
     def step_rec(bank):
-        st = lib.wo_reconstruct(arr, 1, api._ptr(bank), api._ptr(d), None, eta, api._ptr(fout),
+        st = lib.wo_linear_band(api.OP_RECONSTRUCT, arr, 1, api._ptr(bank), api._ptr(d), None, eta,
+                                api._ptr(fout), api._ptr(ws_rec), ws_rec.numel(), sp)
+        assert st == 0, st
+
+    def full_layout_step():
+        st = lib.wo_transfer_function(arr, 1, api._ptr(tf_buf), api._ptr(ws_tf), ws_tf.numel(), sp)
+        assert st == 0, st
+        st = lib.wo_reconstruct(arr, 1, api._ptr(tf_buf), api._ptr(d), None, eta, api._ptr(fout),
                                 api._ptr(ws_rec), ws_rec.numel(), sp)
         assert st == 0, st
 
     ws_both = torch.empty(api.workspace_size([o], api.OP_TF_RECONSTRUCT), dtype=torch.uint8, device=dev)
 
     def full_step():
-        # TF synthesis and reconstruction in one call: the data's X and Y
-        # transforms run on the library's second stream beside the synthesis
+        step_tf()
+        step_rec(tf_band)
+
+    def overlapped_step():
+        # the same in one call, the data's X and Y transforms on the library's
+        # second stream beside the synthesis (secondary figure)
         st = lib.wo_transfer_function_reconstruct(arr, 1, api._ptr(tf_buf), api._ptr(d), None, eta,
                                                   api._ptr(fout), api._ptr(ws_both), ws_both.numel(), sp)
         assert st == 0, st
@@ -330,13 +348,10 @@ def main():
     print(f"[bench] fft schedules: {tuner}", file=sys.stderr, flush=True)
 
     # ---- per-kernel pass: K steps with every library kernel bracketed by HIP events
-    # (the events add gaps between launches, so this pass is not the timed one).
-    # The same kernels as two calls on one stream: each duration is the kernel's
-    # own, not stretched by kernels of the other stream running beside it.
+    # (the events add gaps between launches, so this pass is not the timed one)
     api.timing_enable(True)
     for _ in range(args.steps):
-        step_tf()
-        step_rec(tf_buf)
+        full_step()
     torch.cuda.synchronize()
     api.timing_enable(False)
     kern = api.timing_report()
@@ -362,17 +377,27 @@ def main():
     torch.cuda.synchronize()
     r0 = time.perf_counter()
     for _ in range(args.steps):
-        step_rec(tf_buf)
+        step_rec(tf_band)
     torch.cuda.synchronize()
     ms_rec = (time.perf_counter() - r0) * 1e3 / args.steps
-    # the same step as two calls on one stream (no overlap), for comparison
+    # the same step with the bank in the full layout (its zeros written)
+    for _ in range(args.warmup):
+        full_layout_step()
     torch.cuda.synchronize()
     r0 = time.perf_counter()
     for _ in range(args.steps):
-        step_tf()
-        step_rec(tf_buf)
+        full_layout_step()
     torch.cuda.synchronize()
-    ms_two_calls = (time.perf_counter() - r0) * 1e3 / args.steps
+    ms_full_layout = (time.perf_counter() - r0) * 1e3 / args.steps
+    # the same step as one overlapped call (wo_transfer_function_reconstruct)
+    for _ in range(args.warmup):
+        overlapped_step()
+    torch.cuda.synchronize()
+    r0 = time.perf_counter()
+    for _ in range(args.steps):
+        overlapped_step()
+    torch.cuda.synchronize()
+    ms_overlapped = (time.perf_counter() - r0) * 1e3 / args.steps
 
     kernels = {}
     step_bytes = 0
@@ -405,11 +430,13 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "label-free 3D phase+absorption, 96x512x512, 1 channel x 2 properties",
+        "config": {"workload": "label-free 3D phase+absorption, 96x512x512, 1 channel x 2 properties "
+                               "(bank kept on its lateral support)",
                    "shape_zyx": [Z, Y, X], "voxel_um": [o.dz, o.dy, o.dx], "eta_rel": ETA_REL},
         "lateral_support": {k: list(v) if isinstance(v, tuple) else v for k, v in sup.items()},
         "reconstruct_cached_tf": {"ms": ms_rec, "voxels_per_s": V / (ms_rec * 1e-3)},
-        "ms_per_step_two_calls_one_stream": ms_two_calls,
+        "ms_per_step_full_layout_bank": ms_full_layout,
+        "ms_per_step_overlapped_call_full_layout": ms_overlapped,
         "fft_schedules": tuner,
         "roofline": roof,
         # every library kernel of the step: algorithmic bytes per step over the

@@ -176,6 +176,24 @@ int wo_forward(const wo_optics* o, int32_t n, const void* tf, const float* f, co
 int wo_reconstruct(const wo_optics* o, int32_t n, const void* tf, const float* d, const float* b,
                    double eta, float* f_out, void* ws, size_t ws_bytes, void* stream);
 
+/* The bank on its lateral support (see wo_lateral_support): [n][C][P][nz][band_rows][tf_cols] complex64, row b of a
+ * plane the bank's row y = b (b <= ky) or ny - band_rows + b, columns
+ * k < tf_cols of the half spectrum; every other value of the full bank is zero
+ * and implied, as the Hermitian half is.  The values are those
+ * wo_transfer_function writes there, bit for bit.  Label-free 3D models
+ * (one or nine apertures), or any 3D model whose support fills the grid (then
+ * the layout is the full one); others: WO_EUNSUPPORTED.  Workspace as for
+ * wo_transfer_function. */
+int wo_transfer_function_band(const wo_optics* o, int32_t n, void* tf_out, void* ws, size_t ws_bytes,
+                              void* stream);
+/* wo_forward (op WO_OP_FORWARD: in = f, out = d, eta ignored), wo_reconstruct
+ * (WO_OP_RECONSTRUCT: in = d, out = f) or wo_adjoint (WO_OP_ADJOINT: in = r,
+ * out = g, b ignored) with the bank in the band layout of
+ * wo_transfer_function_band; results bit for bit those of the full-layout
+ * call.  3D models only (thin: WO_EUNSUPPORTED); workspace as for those calls. */
+int wo_linear_band(int32_t op, const wo_optics* o, int32_t n, const void* tf, const float* in,
+                   const float* b, double eta, float* out, void* ws, size_t ws_bytes, void* stream);
+
 /* Transfer-function synthesis followed by the Tikhonov reconstruction with
  * that bank -- wo_transfer_function(o, n, tf_out, ...) then wo_reconstruct(o,
  * n, tf_out, d, b, eta, f_out, ...), same arguments, results and errors -- in

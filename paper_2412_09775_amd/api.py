@@ -40,7 +40,8 @@ SYMBOLS = ("wo_bank_shape", "wo_workspace_size", "wo_transfer_function", "wo_for
            "wo_synth_thin_cells", "wo_add_gaussian_noise", "wo_crop_stacks", "wo_fft_tune",
            "wo_fft_plans_export", "wo_fft_plans_import", "wo_fft_plans_clear", "wo_fft_candidates",
            "wo_tile_grid", "wo_stitch_tiles", "wo_timing_select", "wo_midband_loss_grad_aberration",
-           "wo_lateral_support", "wo_transfer_function_reconstruct")
+           "wo_lateral_support", "wo_transfer_function_reconstruct", "wo_transfer_function_band",
+           "wo_linear_band")
 
 _FIELDS = ("model", "nz", "ny", "nx", "dz", "dy", "dx", "wavelength", "na_ill", "na_det",
            "n_medium", "defocus", "tilt_zenith", "tilt_azimuth", "edge_width", "swing")
@@ -123,6 +124,8 @@ def load(path: str = LIB_PATH):
     lib.wo_reconstruct.argtypes = [op, i32, vp, vp, vp, ctypes.c_double, vp, vp, sz, vp]
     lib.wo_adjoint.argtypes = [op, i32, vp, vp, vp, vp, sz, vp]
     lib.wo_transfer_function_reconstruct.argtypes = [op, i32, vp, vp, vp, ctypes.c_double, vp, vp, sz, vp]
+    lib.wo_transfer_function_band.argtypes = [op, i32, vp, vp, sz, vp]
+    lib.wo_linear_band.argtypes = [i32, op, i32, vp, vp, vp, ctypes.c_double, vp, vp, sz, vp]
     lib.wo_strerror.argtypes = [ctypes.c_int]
     lib.wo_strerror.restype = ctypes.c_char_p
     lib.wo_version.restype = ctypes.c_int
@@ -318,6 +321,43 @@ def transfer_function_reconstruct(optics, d, eta, b=None, tf=None, out=None, ws=
                                                 _ptr(out), _ptr(ws), ws.numel(), _stream(stream)),
            "wo_transfer_function_reconstruct")
     return out, tf
+
+
+def band_dims(optics):
+    """Tensor shape of one call's bank in the band layout: (n, C, P, Z, band rows, columns)."""
+    arr = optics_array(optics)
+    C, P, dims, _ = bank_shape(optics)
+    sup = lateral_support(optics)
+    return (len(arr), C, P, arr[0].nz, sup["band_rows"], sup["tf_cols"])
+
+
+def transfer_function_band(optics, device="cuda", out=None, ws=None, stream=None):
+    """TF bank on its lateral support (``wo_transfer_function_band``)."""
+    import torch
+    lib = load()
+    arr = optics_array(optics)
+    if out is None:
+        out = torch.empty(band_dims(optics), dtype=torch.complex64, device=device)
+    ws, _ = _workspace(optics, OP_TRANSFER_FUNCTION, out.device, ws)
+    _check(lib.wo_transfer_function_band(arr, len(arr), _ptr(out), _ptr(ws), ws.numel(), _stream(stream)),
+           "wo_transfer_function_band")
+    return out
+
+
+def linear_band(op, optics, tf_band, x, eta=0.0, b=None, ws=None, stream=None):
+    """Forward, reconstruction or adjoint (op OP_FORWARD / OP_RECONSTRUCT / OP_ADJOINT)
+    with a band-layout bank (``wo_linear_band``)."""
+    import torch
+    lib = load()
+    arr = optics_array(optics)
+    C, P, dims, _ = bank_shape(optics)
+    nout = C if op == OP_FORWARD else P
+    out = torch.empty((len(arr), nout) + _vol(optics), dtype=torch.float32, device=x.device)
+    ws, _ = _workspace(optics, op, x.device, ws)
+    _check(lib.wo_linear_band(op, arr, len(arr), _ptr(tf_band), _ptr(x.contiguous()), _ptr(b),
+                              ctypes.c_double(eta), _ptr(out), _ptr(ws), ws.numel(), _stream(stream)),
+           "wo_linear_band")
+    return out
 
 
 def adjoint(optics, tf, r, ws=None, stream=None):

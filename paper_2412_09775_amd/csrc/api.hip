@@ -438,8 +438,11 @@ int linear_in(const wo_optics* o, int32_t n, const Shape& s, const float* in, in
   return WO_OK;
 }
 
+// bank_band: tf holds the band layout ([C][P][Z][band rows][kt], see
+// wo_transfer_function_band) instead of [C][P][Z][Y][Xh]; the two coincide
+// where the support fills the grid.
 int linear_out(const wo_optics* o, int32_t n, const Shape& s, const float2* tf, float* out,
-               const float* bg, int mode, float eta, void* ws, hipStream_t st) {
+               const float* bg, int mode, float eta, void* ws, hipStream_t st, bool bank_band = false) {
   const LinearPlan p = linear_plan(o, n, s, mode);
   float2* spec = (float2*)ws;
   const long M = s.Y * s.Xh;
@@ -447,7 +450,7 @@ int linear_out(const wo_optics* o, int32_t n, const Shape& s, const float2* tf, 
   const float inv_n = (float)(1.0 / nfull);
   RowGroups gout{p.cout * p.zd * s.Y, p.CH * p.zd * s.Y, p.cout * p.zd * s.Y, n};
   if (p.banded) {
-    const SpecBand band{(int)s.Y, p.kt, p.ky};
+    const SpecBand band{(int)s.Y, p.kt, p.ky, bank_band ? 1 : 0};
     WO_TRY(launch_zop(spec, tf, s.C, s.P, (int)s.Z, M, p.CH, n, mode, eta, bg, inv_n, nfull, st, &band));
     WO_TRY(launch_cols(spec, (int)s.Y, p.kt, p.cout * p.zd, p.CH * p.zd, n, 1.f, st, "k_cols_y_inv", 2,
                        p.ky));
@@ -465,10 +468,11 @@ int linear_out(const wo_optics* o, int32_t n, const Shape& s, const float2* tf, 
 }
 
 int run_linear(const wo_optics* o, int32_t n, const Shape& s, const float2* tf, const float* in,
-               float* out, const float* bg, int mode, float eta, void* ws, hipStream_t st) {
+               float* out, const float* bg, int mode, float eta, void* ws, hipStream_t st,
+               bool bank_band = false) {
   int r = linear_in(o, n, s, in, mode, ws, st);
   if (r) return r;
-  return linear_out(o, n, s, tf, out, bg, mode, eta, ws, st);
+  return linear_out(o, n, s, tf, out, bg, mode, eta, ws, st, bank_band);
 }
 
 // A second stream per device (default priority, created on first use, kept
@@ -1131,7 +1135,8 @@ int wo_lateral_support(const wo_optics* o, int32_t n, wo_support* out) {
 
 // Transfer-function synthesis of validated optics into tf_out (workspace
 // tf_ws bytes at ws).
-static int run_tf(const wo_optics* o, int32_t n, const Shape& s, void* tf_out, void* ws, hipStream_t hs) {
+static int run_tf(const wo_optics* o, int32_t n, const Shape& s, void* tf_out, void* ws, hipStream_t hs,
+                  bool band_out = false) {
   const int fs = field_sets(o);
   const int nv = n * fs;          // field sets: patch i, aperture c at i * fs + c
   std::vector<DevOptics> h(nv);
@@ -1160,6 +1165,9 @@ static int run_tf(const wo_optics* o, int32_t n, const Shape& s, void* tf_out, v
   // field buffer behind the compact fields.
   bool compact_out = false;
   LatSupport sup = tf_support(o, n, s, &compact_out);
+  // the band layout is the full one where the support fills the grid; else it
+  // comes from the compact Z pass of the label-free 3D models
+  if (band_out && !compact_out && (s.thin || sup.kt < s.Xh || sup.ky < s.Y)) return WO_EUNSUPPORTED;
   float2* tf = (float2*)tf_out;
   const long M = s.Y * s.Xh;
   const long plane = s.Y * s.Xh;
@@ -1180,7 +1188,7 @@ static int run_tf(const wo_optics* o, int32_t n, const Shape& s, void* tf_out, v
                                         hs, &sup, sup.kt));
         WO_TRY(launch_cols(cb, sup.ly, sup.kt, 2 * s.Z, 2 * s.Z, n, -1.f, hs, "k_cols_y_tf", 1, sup.ky));
         WO_TRY(launch_cols_expand(cb, tf, (int)s.Z, sup.ly, (int)s.Y, (int)s.Xh, sup.kt, sup.ky, 2L * n,
-                                  -1.f, hs));
+                                  -1.f, hs, band_out));
       } else {
         WO_TRY(launch_tf_rows_labelfree(partials, sm, n, ab, tf, 2 * s.Z * plane, s.Z * plane, plane, hs,
                                         &full_out));
@@ -1200,7 +1208,7 @@ static int run_tf(const wo_optics* o, int32_t n, const Shape& s, void* tf_out, v
                                         sup.kt));
         WO_TRY(launch_cols(cb, sup.ly, sup.kt, s.Z, s.Z, nv, -1.f, hs, "k_cols_y_tf", 1, sup.ky));
         WO_TRY(launch_cols_expand(cb, tf, (int)s.Z, sup.ly, (int)s.Y, (int)s.Xh, sup.kt, sup.ky, nv, -1.f,
-                                  hs));
+                                  hs, band_out));
       } else {
         WO_TRY(launch_tf_rows_labelfree(partials, sm, nv, ab, tf, s.Z * plane, -1, plane, hs, &full_out));
         WO_TRY(launch_cols(tf, (int)s.Y, s.Xh, s.Z, s.Z, nv, -1.f, hs, "k_cols_y_tf"));
@@ -1230,6 +1238,41 @@ int wo_transfer_function(const wo_optics* o, int32_t n, void* tf_out, void* ws, 
   bank_shape(o, &s);
   if (ws_bytes < tf_ws(o, n, s)) return WO_ENOMEM;
   return run_tf(o, n, s, tf_out, ws, (hipStream_t)stream);
+}
+
+int wo_transfer_function_band(const wo_optics* o, int32_t n, void* tf_out, void* ws, size_t ws_bytes,
+                              void* stream) {
+  int st = validate(o, n);
+  if (st) return st;
+  if (!tf_out || !ws) return WO_EINVAL;
+  Shape s;
+  bank_shape(o, &s);
+  if (ws_bytes < tf_ws(o, n, s)) return WO_ENOMEM;
+  return run_tf(o, n, s, tf_out, ws, (hipStream_t)stream, true);
+}
+
+int wo_linear_band(int32_t op, const wo_optics* o, int32_t n, const void* tf, const float* in,
+                   const float* b, double eta, float* out, void* ws, size_t ws_bytes, void* stream) {
+  if (!o || n < 1) return WO_EINVAL;
+  if (op != WO_OP_FORWARD && op != WO_OP_RECONSTRUCT && op != WO_OP_ADJOINT) return WO_EINVAL;
+  int st = check_sampling(o);
+  if (st) return st;
+  for (int i = 1; i < n; ++i)
+    if (!same_sampling(&o[0], &o[i])) return WO_EINVAL;
+  if (!tf || !in || !out || !ws) return WO_EINVAL;
+  Shape s;
+  bank_shape(o, &s);
+  if (s.thin) return WO_EUNSUPPORTED;
+  if (s.P != 1 && s.P != 2 && s.P != 4) return WO_EUNSUPPORTED;
+  if (!zop_fits((int)s.Z, std::max(s.C, s.P))) return WO_EUNSUPPORTED;
+  const int mode = op == WO_OP_FORWARD ? kModeForward : (op == WO_OP_RECONSTRUCT ? kModeSolve : kModeAdjoint);
+  if (mode == kModeSolve) {
+    if (!(eta >= 0.0) || !isfinite(eta)) return WO_EINVAL;
+    if (eta == 0.0 && s.P != 1) return WO_EUNSUPPORTED;
+  }
+  if (ws_bytes < linear_ws(n, s)) return WO_ENOMEM;
+  return run_linear(o, n, s, (const float2*)tf, in, out, mode == kModeAdjoint ? nullptr : b, mode,
+                    mode == kModeSolve ? (float)eta : 0.f, ws, (hipStream_t)stream, true);
 }
 
 int wo_forward(const wo_optics* o, int32_t n, const void* tf, const float* f, const float* b,

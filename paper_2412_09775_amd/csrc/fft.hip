@@ -406,7 +406,8 @@ __global__ __launch_bounds__(1024) void k_cols_expand(const float2* __restrict__
                                                       float2* __restrict__ dst, int N, int Ys, int Y,
                                                       int Xh, int kt, int ky, int nb, int Wrt,
                                                       int tiles_row, long tiles_g, long zrows,
-                                                      long zrows_total, FftPlan plan, float sign) {
+                                                      long zrows_total, int band_out, FftPlan plan,
+                                                      float sign) {
   const int W = WS > 0 ? WS : Wrt;   // a power of two
   const int wsh = WS > 0 ? pow2_shift(WS) : pow2_shift(Wrt);
   extern __shared__ float2 smem[];
@@ -420,9 +421,10 @@ __global__ __launch_bounds__(1024) void k_cols_expand(const float2* __restrict__
   const int ys = band_row(b, ky, nb, Ys), y = band_row(b, ky, nb, Y);
   const int kx0 = j * W;
   const int weff = min(W, kt - kx0);
-  const long ms = (long)Ys * kt, md = (long)Y * Xh;   // plane pitches
+  // plane pitches; a band-layout destination holds the band rows in order
+  const long ms = (long)Ys * kt, md = band_out ? (long)nb * kt : (long)Y * Xh;
   const float2* sb = src + g * N * ms + (long)ys * kt + kx0;
-  float2* db = dst + g * N * md + (long)y * Xh + kx0;
+  float2* db = dst + g * N * md + (band_out ? (long)b * kt : (long)y * Xh) + kx0;
   const int Nc = NS > 0 ? NS : N;
   auto mid = [&] {
     fill_twiddles(tw, Nc, tid, nthr);
@@ -456,7 +458,7 @@ __global__ __launch_bounds__(1024) void k_cols_expand(const float2* __restrict__
 }
 
 hipError_t launch_cols_expand(const float2* src, float2* dst, int N, int Ys, int Y, int Xh, int kt,
-                              int ky, long ngroups, float sign, hipStream_t s) {
+                              int ky, long ngroups, float sign, hipStream_t s, bool band_out) {
   if (kt < 1 || kt > Xh || ky < 0 || Ys < 1 || Ys > Y) return hipErrorInvalidValue;
   const int nb = 2L * ky + 1 < Y ? 2 * ky + 1 : Y;
   if (nb > Ys || (nb == Y && Ys != Y)) return hipErrorInvalidValue;   // the band fits both
@@ -470,19 +472,20 @@ hipError_t launch_cols_expand(const float2* src, float2* dst, int N, int Ys, int
   const long nwg = tiles_g * ngroups;
   const int thr = c.threads;
   const size_t lds = (size_t)(N + N * W) * sizeof(float2);
-  const long zrows_total = ngroups * N * (long)Y;
+  const long zrows_total = band_out ? 0 : ngroups * N * (long)Y;   // rows with zeros to write
   const long zrows = (zrows_total + nwg - 1) / nwg;
-  ScopedTiming _t("k_cols_expand", s);
+  const int bo = band_out ? 1 : 0;
+  ScopedTiming _t(band_out ? "k_cols_z_band" : "k_cols_expand", s);
 #define X_(NN)                                                                                  \
   case NN:                                                                                      \
     if (W == static_tile_width(NN))                                                             \
       hipLaunchKernelGGL((k_cols_expand<NN, static_tile_width(NN)>), dim3((unsigned)nwg), dim3(thr), \
                          lds, s, src, dst, N, Ys, Y, Xh, kt, kyn, nb, W, tiles_row, tiles_g,     \
-                         zrows, zrows_total, plan, sign);                                       \
+                         zrows, zrows_total, bo, plan, sign);                                   \
     else                                                                                        \
       hipLaunchKernelGGL((k_cols_expand<NN, 0>), dim3((unsigned)nwg), dim3(thr), lds, s, src, dst, N, \
-                         Ys, Y, Xh, kt, kyn, nb, W, tiles_row, tiles_g, zrows, zrows_total, plan,   \
-                         sign);                                                                 \
+                         Ys, Y, Xh, kt, kyn, nb, W, tiles_row, tiles_g, zrows, zrows_total, bo,     \
+                         plan, sign);                                                           \
     return hipGetLastError();
   if (c.plan == 0) switch (N) {
       WO_AXIAL_SIZES(X_)
@@ -491,7 +494,7 @@ hipError_t launch_cols_expand(const float2* src, float2* dst, int N, int Ys, int
     }
 #undef X_
   hipLaunchKernelGGL((k_cols_expand<0, 0>), dim3((unsigned)nwg), dim3(thr), lds, s, src, dst, N, Ys, Y,
-                     Xh, kt, kyn, nb, W, tiles_row, tiles_g, zrows, zrows_total, plan, sign);
+                     Xh, kt, kyn, nb, W, tiles_row, tiles_g, zrows, zrows_total, bo, plan, sign);
   return hipGetLastError();
 }
 
@@ -607,12 +610,13 @@ constexpr int kTfPrefetch = 8;   // transfer-function values a thread may hold i
 
 // Geometry of the fused Z pass.  A plane of the spectrum holds R rows of row
 // pitch Ls (plane pitch Ms), a plane of the bank R rows of pitch Lt (plane
-// pitch Mt); the pass covers the columns k < kt of the band rows (band_row:
-// ky, nb) in tiles of W columns that do not cross a row.  The plain layout is
-// one row: R = 1, Ls = Lt = kt = Ms = Mt = M, nb = 1.
+// pitch Mt), or only the band rows in band order (bank_band); the pass covers
+// the columns k < kt of the band rows (band_row: ky, nb) in tiles of W columns
+// that do not cross a row.  The plain layout is one row: R = 1,
+// Ls = Lt = kt = Ms = Mt = M, nb = 1.
 struct ZopGeom {
   long Ms, Mt, Ls, Lt, kt;
-  int R, ky, nb, tiles_row;
+  int R, ky, nb, tiles_row, bank_band;
 };
 
 template <int P, int CT, int NS>
@@ -641,7 +645,7 @@ __global__ __launch_bounds__(1024) void k_zop(float2* __restrict__ spec,
   const long col0 = (tile - (long)brow * gm.tiles_row) * W;
   const int row = band_row(brow, gm.ky, gm.nb, gm.R);
   const long m0 = row * gm.Ls + col0;        // tile start in a spectrum plane
-  const long mt0 = row * gm.Lt + col0;       // and in a bank plane
+  const long mt0 = (gm.bank_band ? brow : row) * gm.Lt + col0;   // and in a bank plane
   const bool dc_tile = row == 0 && col0 == 0;
   const int weff = (int)min((long)W, gm.kt - col0);
   const long ts = (long)Z * Mt;              // stride between (c, p) entries of the bank
@@ -798,7 +802,7 @@ hipError_t launch_zop(float2* spec, const float2* tf, int C, int P, int Z, long 
                band->ky < 0))
     return hipErrorInvalidValue;
   const bool hb = band != nullptr;
-  const SpecBand bc = hb ? *band : SpecBand{1, M, 0};
+  const SpecBand bc = hb ? *band : SpecBand{1, M, 0, 0};
   const int nbr = hb ? (2L * bc.ky + 1 >= bc.Y ? bc.Y : 2 * bc.ky + 1) : 1;
   const long mcov = hb ? (long)nbr * bc.kt : M;   // columns the pass covers per plane
   const FftKey key{kFftZop, Z, mcov, npatch, P * 1000 + C * 10 + mode + (hb ? 100000 : 0)};
@@ -819,9 +823,10 @@ hipError_t launch_zop(float2* spec, const float2* tf, int C, int P, int Z, long 
   gm.R = bc.Y;
   gm.kt = bc.kt;
   gm.Ls = bc.kt;
-  gm.Lt = M / bc.Y;
+  gm.bank_band = hb && bc.bank_band;
+  gm.Lt = gm.bank_band ? bc.kt : M / bc.Y;
   gm.Ms = (long)bc.Y * bc.kt;
-  gm.Mt = M;
+  gm.Mt = gm.bank_band ? (long)nbr * bc.kt : M;
   gm.nb = nbr;
   gm.ky = nbr == bc.Y ? bc.Y : bc.ky;
   gm.tiles_row = (int)((bc.kt + W - 1) / W);

@@ -117,9 +117,10 @@ hipError_t launch_cols(float2* data, int N, long M, long planes_per_group, long 
 // FFT along N of the band rows (y <= ky or y >= rows - ky) of compact planes
 // src [g][N][Ys][kt] into the full half-spectrum planes dst [g][N][Y][Xh];
 // every other value of dst (rows outside the band, columns kx >= kt) is set
-// to zero.
+// to zero.  band_out: dst planes hold the band rows only, [g][N][nb][kt] in
+// band order (no zeros written).
 hipError_t launch_cols_expand(const float2* src, float2* dst, int N, int Ys, int Y, int Xh, int kt,
-                              int ky, long ngroups, float sign, hipStream_t s);
+                              int ky, long ngroups, float sign, hipStream_t s, bool band_out = false);
 
 enum SpectralMode { kModeForward = 0, kModeSolve = 1, kModeAdjoint = 2 };
 
@@ -127,10 +128,13 @@ enum SpectralMode { kModeForward = 0, kModeSolve = 1, kModeAdjoint = 2 };
 bool zop_fits(int Z, int CH);
 // Lateral band of a compact spectrum: planes of Y rows holding the
 // half-spectrum columns k < kt; the band rows are y <= ky and y >= Y - ky.
+// bank_band: the bank, too, holds only the band rows (in band order) of kt
+// columns per plane instead of Y rows of Xh.
 struct SpecBand {
   int Y;
   long kt;
   int ky;
+  int bank_band;
 };
 // 3D: forward Z-FFT, per-frequency op, inverse Z-FFT, fused.  spec holds
 // `slots` channel slots of [Z][M] per patch; tf holds [C][P][Z][M] per patch.

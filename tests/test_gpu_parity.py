@@ -296,3 +296,63 @@ def test_overlapped_synthesis_and_reconstruction_equals_the_two_calls(gpu_lib, t
         err = rel_l2(got[i], linear.reconstruct(banks[i], ds[i], None, eta))
         print(f"  patch {i}: rel L2 = {err:.3e}")
         assert err < TOL_REC
+
+
+def band_slice(torch, full, sup, ny):
+    """The band layout cut from a full-layout bank (n, C, P, Z, Y, Xh)."""
+    nb, kt = sup["band_rows"], sup["tf_cols"]
+    ky = (nb - 1) // 2
+    rows = list(range(ky + 1)) + list(range(ny - ky, ny)) if nb < ny else list(range(ny))
+    return full[..., rows, :kt].contiguous(), rows
+
+
+@pytest.mark.parametrize("name", ["labelfree_3d", "labelfree_3d_band_batch2", "labelfree_3d_short_transforms",
+                                  "sectors9_band", "labelfree_3d_aberrated"])
+def test_band_bank_is_the_full_bank_on_its_support(gpu_lib, torch, name):
+    """wo_transfer_function_band writes bit for bit the values of the full bank on
+    the support; the full bank is exactly zero off it."""
+    opts = CASES[name]
+    print(f"[case] band bank {name}", flush=True)
+    sup = gpu_lib.lateral_support(opts)
+    full = gpu_lib.transfer_function(opts)
+    band = gpu_lib.transfer_function_band(opts)
+    cut, rows = band_slice(torch, full, sup, opts[0].ny)
+    assert tuple(band.shape) == tuple(cut.shape)
+    assert torch.equal(band, cut)
+    rest = full.clone()
+    rest[..., rows, :sup["tf_cols"]] = 0
+    assert int(torch.count_nonzero(rest)) == 0
+
+
+@pytest.mark.parametrize("name", ["labelfree_3d_band_batch2", "labelfree_3d_short_transforms", "sectors9_band",
+                                  "fluor_cfg1", "pol5"])
+def test_linear_calls_with_the_band_bank_equal_the_full_bank(gpu_lib, torch, name):
+    """wo_linear_band (forward, reconstruction, adjoint) with the band layout cut from
+    the full bank gives bit for bit the full-layout calls' results."""
+    opts = CASES[name]
+    print(f"[case] linear band {name}", flush=True)
+    sup = gpu_lib.lateral_support(opts)
+    full = gpu_lib.transfer_function(opts)
+    band, _ = band_slice(torch, full, sup, opts[0].ny)
+    C, P, _, _ = gpu_lib.bank_shape(opts)
+    vol = (opts[0].nz, opts[0].ny, opts[0].nx)
+    g = torch.Generator(device="cuda").manual_seed(7)
+    f = torch.randn((len(opts), P) + vol, device="cuda", generator=g)
+    d = torch.randn((len(opts), C) + vol, device="cuda", generator=g)
+    b = torch.linspace(0.1, 0.2, len(opts) * C, device="cuda").reshape(len(opts), C)
+    eta = 1e-2
+    assert torch.equal(gpu_lib.linear_band(gpu_lib.OP_FORWARD, opts, band, f, b=b),
+                       gpu_lib.forward(opts, full, f, b=b))
+    assert torch.equal(gpu_lib.linear_band(gpu_lib.OP_RECONSTRUCT, opts, band, d, eta=eta, b=b),
+                       gpu_lib.reconstruct(opts, full, d, eta, b=b))
+    assert torch.equal(gpu_lib.linear_band(gpu_lib.OP_ADJOINT, opts, band, d),
+                       gpu_lib.adjoint(opts, full, d))
+
+
+def test_band_synthesis_of_models_without_the_compact_path_is_unsupported(gpu_lib, torch):
+    o = CASES["pol5"][0]
+    sup = gpu_lib.lateral_support([o])
+    if sup["tf_cols"] == o.nx // 2 + 1 and sup["band_rows"] == o.ny:
+        pytest.skip("support fills the grid: the band layout is the full one")
+    with pytest.raises(gpu_lib.WoError):
+        gpu_lib.transfer_function_band([o])
