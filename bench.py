@@ -206,6 +206,9 @@ def main():
     ap.add_argument("--fov-size", type=int, default=2048, help="field of view side (0: skip)")
     ap.add_argument("--no-multi-aperture", action="store_true")
     ap.add_argument("--no-aberration", action="store_true")
+    ap.add_argument("--main-only", action="store_true",
+                    help="skip the full-layout and overlapped-call comparisons (profiled runs: only "
+                         "the bench step's kernels in the trace)")
     ap.add_argument("--no-fft-tune", action="store_true", help="keep the default FFT schedules")
     ap.add_argument("--fft-plans", default="", help="import an FFT schedule table instead of tuning")
     ap.add_argument("--save-fft-plans", default="", help="write the FFT schedule table used")
@@ -381,23 +384,26 @@ def main():
     torch.cuda.synchronize()
     ms_rec = (time.perf_counter() - r0) * 1e3 / args.steps
     # the same step with the bank in the full layout (its zeros written)
-    for _ in range(args.warmup):
-        full_layout_step()
-    torch.cuda.synchronize()
-    r0 = time.perf_counter()
-    for _ in range(args.steps):
-        full_layout_step()
-    torch.cuda.synchronize()
-    ms_full_layout = (time.perf_counter() - r0) * 1e3 / args.steps
+    ms_full_layout = ms_overlapped = None
+    if not args.main_only:
+        for _ in range(args.warmup):
+            full_layout_step()
+        torch.cuda.synchronize()
+        r0 = time.perf_counter()
+        for _ in range(args.steps):
+            full_layout_step()
+        torch.cuda.synchronize()
+        ms_full_layout = (time.perf_counter() - r0) * 1e3 / args.steps
     # the same step as one overlapped call (wo_transfer_function_reconstruct)
-    for _ in range(args.warmup):
-        overlapped_step()
-    torch.cuda.synchronize()
-    r0 = time.perf_counter()
-    for _ in range(args.steps):
-        overlapped_step()
-    torch.cuda.synchronize()
-    ms_overlapped = (time.perf_counter() - r0) * 1e3 / args.steps
+    if not args.main_only:
+        for _ in range(args.warmup):
+            overlapped_step()
+        torch.cuda.synchronize()
+        r0 = time.perf_counter()
+        for _ in range(args.steps):
+            overlapped_step()
+        torch.cuda.synchronize()
+        ms_overlapped = (time.perf_counter() - r0) * 1e3 / args.steps
 
     kernels = {}
     step_bytes = 0
