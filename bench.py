@@ -207,8 +207,8 @@ def main():
     ap.add_argument("--no-multi-aperture", action="store_true")
     ap.add_argument("--no-aberration", action="store_true")
     ap.add_argument("--main-only", action="store_true",
-                    help="skip the full-layout and overlapped-call comparisons (profiled runs: only "
-                         "the bench step's kernels in the trace)")
+                    help="skip the full-layout comparison (profiled runs: only the bench step's "
+                         "kernels in the trace)")
     ap.add_argument("--no-fft-tune", action="store_true", help="keep the default FFT schedules")
     ap.add_argument("--fft-plans", default="", help="import an FFT schedule table instead of tuning")
     ap.add_argument("--save-fft-plans", default="", help="write the FFT schedule table used")
@@ -271,8 +271,8 @@ def main():
     sp = api._stream(stream)
 
     # The step keeps the bank on its lateral support (band layout: the values off
-    # it are zero and implied, like the Hermitian half); the full-layout bank
-    # and the one-call overlapped variant are timed as secondary figures.
+    # it are zero and implied, like the Hermitian half); the full-layout bank is
+    # timed as a secondary figure.
     tf_band = torch.empty(api.band_dims([o]), dtype=torch.complex64, device=dev)
 
     def step_tf():
@@ -291,18 +291,9 @@ def main():
                                 api._ptr(ws_rec), ws_rec.numel(), sp)
         assert st == 0, st
 
-    ws_both = torch.empty(api.workspace_size([o], api.OP_TF_RECONSTRUCT), dtype=torch.uint8, device=dev)
-
     def full_step():
         step_tf()
         step_rec(tf_band)
-
-    def overlapped_step():
-        # the same in one call, the data's X and Y transforms on the library's
-        # second stream beside the synthesis (secondary figure)
-        st = lib.wo_transfer_function_reconstruct(arr, 1, api._ptr(tf_buf), api._ptr(d), None, eta,
-                                                  api._ptr(fout), api._ptr(ws_both), ws_both.numel(), sp)
-        assert st == 0, st
 
     for _ in range(args.warmup):
         full_step()
@@ -384,7 +375,7 @@ def main():
     torch.cuda.synchronize()
     ms_rec = (time.perf_counter() - r0) * 1e3 / args.steps
     # the same step with the bank in the full layout (its zeros written)
-    ms_full_layout = ms_overlapped = None
+    ms_full_layout = None
     if not args.main_only:
         for _ in range(args.warmup):
             full_layout_step()
@@ -394,16 +385,6 @@ def main():
             full_layout_step()
         torch.cuda.synchronize()
         ms_full_layout = (time.perf_counter() - r0) * 1e3 / args.steps
-    # the same step as one overlapped call (wo_transfer_function_reconstruct)
-    if not args.main_only:
-        for _ in range(args.warmup):
-            overlapped_step()
-        torch.cuda.synchronize()
-        r0 = time.perf_counter()
-        for _ in range(args.steps):
-            overlapped_step()
-        torch.cuda.synchronize()
-        ms_overlapped = (time.perf_counter() - r0) * 1e3 / args.steps
 
     kernels = {}
     step_bytes = 0
@@ -442,7 +423,6 @@ def main():
         "lateral_support": {k: list(v) if isinstance(v, tuple) else v for k, v in sup.items()},
         "reconstruct_cached_tf": {"ms": ms_rec, "voxels_per_s": V / (ms_rec * 1e-3)},
         "ms_per_step_full_layout_bank": ms_full_layout,
-        "ms_per_step_overlapped_call_full_layout": ms_overlapped,
         "fft_schedules": tuner,
         "roofline": roof,
         # every library kernel of the step: algorithmic bytes per step over the

@@ -87,8 +87,7 @@ enum {
   WO_OP_TRANSFER_FUNCTION = 0,
   WO_OP_FORWARD = 1,
   WO_OP_RECONSTRUCT = 2,
-  WO_OP_ADJOINT = 3,
-  WO_OP_TF_RECONSTRUCT = 4   /* wo_transfer_function_reconstruct */
+  WO_OP_ADJOINT = 3
 };
 
 /* Optics and sampling of one patch (Ext. Data Fig. 3: calc_ill_pupil takes
@@ -193,17 +192,6 @@ int wo_transfer_function_band(const wo_optics* o, int32_t n, void* tf_out, void*
  * call.  3D models only (thin: WO_EUNSUPPORTED); workspace as for those calls. */
 int wo_linear_band(int32_t op, const wo_optics* o, int32_t n, const void* tf, const float* in,
                    const float* b, double eta, float* out, void* ws, size_t ws_bytes, void* stream);
-
-/* Transfer-function synthesis followed by the Tikhonov reconstruction with
- * that bank -- wo_transfer_function(o, n, tf_out, ...) then wo_reconstruct(o,
- * n, tf_out, d, b, eta, f_out, ...), same arguments, results and errors -- in
- * one call that overlaps the two: the data's X and Y transforms run on a
- * second stream the library keeps per device (default priority), forked from
- * and joined back into `stream` with events, beside the synthesis.  Workspace:
- * wo_workspace_size(o, n, WO_OP_TF_RECONSTRUCT) bytes. */
-int wo_transfer_function_reconstruct(const wo_optics* o, int32_t n, void* tf_out, const float* d,
-                                     const float* b, double eta, float* f_out, void* ws,
-                                     size_t ws_bytes, void* stream);
 
 /* Adjoint g_p = IFFT(sum_c conj(H_cp) R_c): r [n][C][vol] -> g_out [n][P][vol]. */
 int wo_adjoint(const wo_optics* o, int32_t n, const void* tf, const float* r, float* g_out,

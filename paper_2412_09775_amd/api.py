@@ -29,7 +29,6 @@ OP_TRANSFER_FUNCTION = 0
 OP_FORWARD = 1
 OP_RECONSTRUCT = 2
 OP_ADJOINT = 3
-OP_TF_RECONSTRUCT = 4
 
 SYMBOLS = ("wo_bank_shape", "wo_workspace_size", "wo_transfer_function", "wo_forward",
            "wo_reconstruct", "wo_adjoint", "wo_strerror", "wo_version", "wo_timing_enable",
@@ -40,7 +39,7 @@ SYMBOLS = ("wo_bank_shape", "wo_workspace_size", "wo_transfer_function", "wo_for
            "wo_synth_thin_cells", "wo_add_gaussian_noise", "wo_crop_stacks", "wo_fft_tune",
            "wo_fft_plans_export", "wo_fft_plans_import", "wo_fft_plans_clear", "wo_fft_candidates",
            "wo_tile_grid", "wo_stitch_tiles", "wo_timing_select", "wo_midband_loss_grad_aberration",
-           "wo_lateral_support", "wo_transfer_function_reconstruct", "wo_transfer_function_band",
+           "wo_lateral_support", "wo_transfer_function_band",
            "wo_linear_band")
 
 _FIELDS = ("model", "nz", "ny", "nx", "dz", "dy", "dx", "wavelength", "na_ill", "na_det",
@@ -123,7 +122,6 @@ def load(path: str = LIB_PATH):
     lib.wo_forward.argtypes = [op, i32, vp, vp, vp, vp, vp, sz, vp]
     lib.wo_reconstruct.argtypes = [op, i32, vp, vp, vp, ctypes.c_double, vp, vp, sz, vp]
     lib.wo_adjoint.argtypes = [op, i32, vp, vp, vp, vp, sz, vp]
-    lib.wo_transfer_function_reconstruct.argtypes = [op, i32, vp, vp, vp, ctypes.c_double, vp, vp, sz, vp]
     lib.wo_transfer_function_band.argtypes = [op, i32, vp, vp, sz, vp]
     lib.wo_linear_band.argtypes = [i32, op, i32, vp, vp, vp, ctypes.c_double, vp, vp, sz, vp]
     lib.wo_strerror.argtypes = [ctypes.c_int]
@@ -302,25 +300,6 @@ def reconstruct(optics, tf, d, eta, b=None, ws=None, stream=None):
     lib = load()
     return _linear(lib.wo_reconstruct, "wo_reconstruct", optics, tf, d.contiguous(), fshape,
                    lambda out: (_ptr(b), ctypes.c_double(eta), _ptr(out)), ws, stream, OP_RECONSTRUCT)
-
-
-def transfer_function_reconstruct(optics, d, eta, b=None, tf=None, out=None, ws=None, stream=None):
-    """TF synthesis, then the Tikhonov reconstruction with it, overlapped in one call
-    (``wo_transfer_function_reconstruct``); returns (f, tf)."""
-    import torch
-    lib = load()
-    arr = optics_array(optics)
-    C, P, dims, _ = bank_shape(optics)
-    d = d.contiguous()
-    if tf is None:
-        tf = torch.empty(bank_dims(optics), dtype=torch.complex64, device=d.device)
-    if out is None:
-        out = torch.empty((len(arr), P) + _vol(optics), dtype=torch.float32, device=d.device)
-    ws, _ = _workspace(optics, OP_TF_RECONSTRUCT, d.device, ws)
-    _check(lib.wo_transfer_function_reconstruct(arr, len(arr), _ptr(tf), _ptr(d), _ptr(b), ctypes.c_double(eta),
-                                                _ptr(out), _ptr(ws), ws.numel(), _stream(stream)),
-           "wo_transfer_function_reconstruct")
-    return out, tf
 
 
 def band_dims(optics):

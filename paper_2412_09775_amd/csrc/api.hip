@@ -475,27 +475,6 @@ int run_linear(const wo_optics* o, int32_t n, const Shape& s, const float2* tf, 
   return linear_out(o, n, s, tf, out, bg, mode, eta, ws, st, bank_band);
 }
 
-// A second stream per device (default priority, created on first use, kept
-// for the life of the process) for work a call runs beside its own stream.
-hipError_t side_stream(hipStream_t* out) {
-  static std::mutex mu;
-  static std::map<int, hipStream_t> streams;
-  int dev = 0;
-  hipError_t e = hipGetDevice(&dev);
-  if (e != hipSuccess) return e;
-  std::lock_guard<std::mutex> lk(mu);
-  auto it = streams.find(dev);
-  if (it == streams.end()) {
-    hipStream_t st;
-    e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
-    if (e != hipSuccess) return e;
-    it = streams.emplace(dev, st).first;
-  }
-  *out = it->second;
-  return hipSuccess;
-}
-
-
 // ---------------------------------------------------------------- auto-tune
 
 // Workspace of one group of equally sampled patches, np patches x starts
@@ -546,7 +525,33 @@ struct TuneGroup {
   size_t base;
   double work;
   int ab = 0;            // aberration-aware kernels (an aberrated patch, or dL/dc wanted)
+  LatSupport sup;        // the fields' columns for every theta the tune may reach
 };
+
+// Lateral support of the auto-tune's fields: whatever NA and tilt the tune
+// reaches, the detection pupil (and the source, within it) stays inside the
+// shell |p| <= n/lambda0, so the shell's columns widened by the soft edge
+// bound the fields, their gradients and the pupils' derivatives in every
+// iteration.  The thin bank is written on the grid's own transforms and
+// columns.
+LatSupport tune_support(const wo_optics* o, const std::vector<int>& idx) {
+  const Sampling sm = sampling_of(&o[idx[0]]);
+  LatSupport ls = full_support(sm);
+  const int X = sm.nx;
+  const double fx1 = 1.0 / (X * sm.dx), dnu = fmin(fx1, 1.0 / (sm.ny * sm.dy));
+  int px = 0;
+  for (int i : idx) {
+    const double q = (o[i].n_medium / o[i].wavelength + o[i].edge_width * dnu) / fx1;
+    if (!(q >= 0.0 && q < X)) return ls;
+    px = std::max(px, (int)floor(q) + 1);
+  }
+  const int xc = (2 * px + 1 + 15) / 16 * 16;
+  if (xc < X) {
+    ls.xc = ls.xa = xc;
+    ls.kp = ls.kpa = px;
+  }
+  return ls;
+}
 
 std::vector<TuneGroup> tune_groups(const wo_optics* o, int32_t n, int32_t starts, size_t* total) {
   std::vector<TuneGroup> g;
@@ -559,6 +564,7 @@ std::vector<TuneGroup> tune_groups(const wo_optics* o, int32_t n, int32_t starts
   }
   size_t b = 0;
   for (auto& t : g) {
+    t.sup = tune_support(o, t.idx);
     t.L = tune_layout(t.rep, (int)t.idx.size(), starts);
     t.base = b;
     b += t.L.total;
@@ -648,14 +654,14 @@ int tune_iteration(const TuneGroup& g, char* ws, int starts, int update, hipStre
   double* gp = (double*)(w + L.off_gp);
   double* ip = (double*)(w + L.off_ip);
   const int nv = L.nv;
-  WO_TRY(launch_tf_fields_y(dopt, sm, nv, ab, pp, hs));
-  WO_TRY(launch_tf_rows_labelfree(pp, sm, nv, ab, bank, 2 * Z * plane, plane, 2 * plane, hs));
+  WO_TRY(launch_tf_fields_y(dopt, sm, nv, ab, pp, hs, &g.sup));
+  WO_TRY(launch_tf_rows_labelfree(pp, sm, nv, ab, bank, 2 * Z * plane, plane, 2 * plane, hs, &g.sup));
   WO_TRY(launch_cols(bank, (int)Y, Xh, 2 * Z, 2 * Z, nv, -1.f, hs, "k_cols_y_tf"));
   WO_TRY(launch_loss_grad(dopt, st, sm, nv, D, bank, lp, starts, hs));
   WO_TRY(launch_cols(bank, (int)Y, Xh, 2 * Z, 2 * Z, nv, 1.f, hs, "k_cols_y_grad"));
-  WO_TRY(launch_tf_rows_bwd(pp, sm, nv, ab, bank, dp, hs));
-  WO_TRY(launch_tf_grad_y(dopt, sm, nv, ab, gp, ip, hs));
-  WO_TRY(launch_adam(dopt, st, sm, nv, pp, lp, dp, gp, ip, update, hs));
+  WO_TRY(launch_tf_rows_bwd(pp, sm, nv, ab, bank, dp, hs, &g.sup));
+  WO_TRY(launch_tf_grad_y(dopt, sm, nv, ab, gp, ip, hs, &g.sup));
+  WO_TRY(launch_adam(dopt, st, sm, nv, pp, lp, dp, gp, ip, update, hs, &g.sup));
   return WO_OK;
 }
 
@@ -680,8 +686,8 @@ int tune_restore(const TuneGroup& g, char* ws, int starts, float* f_out, const s
   double* pp = (double*)(w + L.off_pp);
   WO_TRY(launch_pick_best((const DevOptics*)(w + L.off_opt), (const TuneState*)(w + L.off_st), starts,
                           np, ropt, reta, hs));
-  WO_TRY(launch_tf_fields_y(ropt, sm, np, ab, pp, hs));
-  WO_TRY(launch_tf_rows_labelfree(pp, sm, np, ab, bank, 2 * Z * plane, plane, 2 * plane, hs));
+  WO_TRY(launch_tf_fields_y(ropt, sm, np, ab, pp, hs, &g.sup));
+  WO_TRY(launch_tf_rows_labelfree(pp, sm, np, ab, bank, 2 * Z * plane, plane, 2 * plane, hs, &g.sup));
   WO_TRY(launch_cols(bank, (int)Y, Xh, 2 * Z, 2 * Z, np, -1.f, hs, "k_cols_y_tf"));
   const double nfull = (double)Y * X;
   WO_TRY(launch_op2d(D, bank, (int)Z, 2, plane, (int)Z, np, kModeSolve, 0.f, nullptr,
@@ -843,8 +849,10 @@ std::string graph_key(const wo_optics* o, int32_t n, const wo_autotune_opts* opt
   k += b;
   for (int i = 0; i < n; ++i) {
     // the aberration-aware kernel variants are part of the graph
-    snprintf(b, sizeof(b), "%d %d %d %a %a %a %d;", o[i].nz, o[i].ny, o[i].nx, o[i].dz, o[i].dy, o[i].dx,
-             aberrated(o[i]) || ((opts->tune_mask >> 4) & 0x7f) ? 1 : 0);
+    // and so are the fields' compact columns (tune_support)
+    snprintf(b, sizeof(b), "%d %d %d %a %a %a %d %a %a %a;", o[i].nz, o[i].ny, o[i].nx, o[i].dz, o[i].dy,
+             o[i].dx, aberrated(o[i]) || ((opts->tune_mask >> 4) & 0x7f) ? 1 : 0, o[i].wavelength,
+             o[i].n_medium, o[i].edge_width);
     k += b;
   }
   return k;
@@ -1109,7 +1117,6 @@ size_t wo_workspace_size(const wo_optics* o, int32_t n, int32_t op) {
   Shape s;
   if (!o || n < 1 || !bank_shape(o, &s)) return 0;
   if (op == WO_OP_TRANSFER_FUNCTION) return tf_ws(o, n, s);
-  if (op == WO_OP_TF_RECONSTRUCT) return tf_ws(o, n, s) + linear_ws(n, s);
   if (op == WO_OP_FORWARD || op == WO_OP_RECONSTRUCT || op == WO_OP_ADJOINT) return linear_ws(n, s);
   return 0;
 }
@@ -1309,43 +1316,6 @@ int wo_reconstruct(const wo_optics* o, int32_t n, const void* tf, const float* d
   if (ws_bytes < linear_ws(n, s)) return WO_ENOMEM;
   return run_linear(o, n, s, (const float2*)tf, d, f_out, b, kModeSolve, (float)eta, ws,
                     (hipStream_t)stream);
-}
-
-int wo_transfer_function_reconstruct(const wo_optics* o, int32_t n, void* tf_out, const float* d,
-                                     const float* b, double eta, float* f_out, void* ws,
-                                     size_t ws_bytes, void* stream) {
-  int st = validate(o, n);
-  if (st) return st;
-  if (!tf_out || !d || !f_out || !ws) return WO_EINVAL;
-  if (!(eta >= 0.0) || !isfinite(eta)) return WO_EINVAL;
-  Shape s;
-  bank_shape(o, &s);
-  if (s.P != 1 && s.P != 2 && s.P != 4) return WO_EUNSUPPORTED;
-  if (!s.thin && !zop_fits((int)s.Z, std::max(s.C, s.P))) return WO_EUNSUPPORTED;
-  if (eta == 0.0 && s.P != 1) return WO_EUNSUPPORTED;
-  const size_t wt = tf_ws(o, n, s);
-  if (ws_bytes < wt + linear_ws(n, s)) return WO_ENOMEM;
-  void* wl = (char*)ws + wt;
-  hipStream_t hs = (hipStream_t)stream, side;
-  if (side_stream(&side) != hipSuccess) return WO_EHIP;
-  // fork: the data's X and Y transforms on the side stream, after the work
-  // already queued on the caller's stream; join before the Z pass
-  hipEvent_t fork, join;
-  if (hipEventCreateWithFlags(&fork, hipEventDisableTiming) != hipSuccess) return WO_EHIP;
-  if (hipEventCreateWithFlags(&join, hipEventDisableTiming) != hipSuccess) {
-    (void)hipEventDestroy(fork);
-    return WO_EHIP;
-  }
-  int r = WO_OK;
-  if (hipEventRecord(fork, hs) != hipSuccess || hipStreamWaitEvent(side, fork, 0) != hipSuccess) r = WO_EHIP;
-  if (!r) r = linear_in(o, n, s, d, kModeSolve, wl, side);
-  if (!r && hipEventRecord(join, side) != hipSuccess) r = WO_EHIP;
-  if (!r) r = run_tf(o, n, s, tf_out, ws, hs);
-  if (!r && hipStreamWaitEvent(hs, join, 0) != hipSuccess) r = WO_EHIP;
-  if (!r) r = linear_out(o, n, s, (const float2*)tf_out, f_out, b, kModeSolve, (float)eta, wl, hs);
-  (void)hipEventDestroy(fork);
-  (void)hipEventDestroy(join);
-  return r;
 }
 
 int wo_adjoint(const wo_optics* o, int32_t n, const void* tf, const float* r, float* g_out,

@@ -124,7 +124,10 @@ long loss_blocks(const Sampling& sm) {
 
 // ------------------------------------------------------------------ backward rows
 
-// ab: [v][2][Z][Y][X] (field 0 = a, 1 = b after the inverse Y pass, complex);
+// ab: [v][2][Z][Y][XC] (field 0 = a, 1 = b after the inverse Y pass, complex,
+// in the compact columns of the field kernel: XC kept, last non-negative KP;
+// the others are zero, and so are u_A, u_B there: only the kept columns are
+// written back);
 // g: [v][Z][2][Y][Xh], the half spectra of dL/dH* after the inverse Y pass.  For
 // each row the kernel forms Gamma = Gamma_phase + i Gamma_abs in one inverse X
 // transform (the two real rows packed into one complex line), then replaces
@@ -137,7 +140,7 @@ __global__ __launch_bounds__(1024) void k_tf_rows_bwd(const double* __restrict__
                                                       float2* __restrict__ ab,
                                                       const float2* __restrict__ g,
                                                       double* __restrict__ dpart, int rows_per_wg,
-                                                      long wg_per_patch, FftPlan plan) {
+                                                      long wg_per_patch, int XC, int KP, FftPlan plan) {
   extern __shared__ float2 smem[];
   __shared__ double red[kMaxThreads / 64];
   __shared__ double ibg_s;
@@ -154,9 +157,12 @@ __global__ __launch_bounds__(1024) void k_tf_rows_bwd(const double* __restrict__
   const long row0 = wg * (long)rows_per_wg;
   const int nr = (int)min((long)rows_per_wg, rpp - row0);
   const int z0 = (int)(row0 / Y), y0 = (int)(row0 - (long)z0 * Y);
-  float2* a_src = ab + (v * 2 + 0) * rpp * X;
-  float2* b_src = ab + (v * 2 + 1) * rpp * X;
+  float2* a_src = ab + (v * 2 + 0) * rpp * XC;
+  float2* b_src = ab + (v * 2 + 1) * rpp * XC;
   const float2* g_src = g + v * rpp * 2 * Xh;
+  const int neg0 = X - (XC - KP - 1);   // first kept negative-frequency column
+  auto kept = [&](int i) { return i <= KP || i >= neg0; };
+  auto ccol = [&](int i) { return i <= KP ? i : max(i - (X - XC), KP); };   // clamped compact column
   const int PS = pad_shift(X);   // row padding
   const int LS = row_stride(X);      // padded line pitch in LDS
   // lines 2r, 2r + 1: a (then u_A), b (then u_B) of row r; line 2 nr + r: Gamma of row r
@@ -164,25 +170,61 @@ __global__ __launch_bounds__(1024) void k_tf_rows_bwd(const double* __restrict__
     const int t = e / X;
     return t * LS + row_slot(e - t * X, PS);
   };
-  gather_to_lds_map(buf, nr * 3 * X, tid, nthr, [&](int e) {
-    const int i = e % X;
-    const int t = e / X;
-    if (t < 2 * nr) {
-      const int f = t & 1, r = t >> 1;
-      return (f ? b_src : a_src)[(row0 + r) * X + i];
+  // All loads of a thread first, then the selections and the Hermitian
+  // extension, so the loads stay in flight together: the field lines (one
+  // load per element), then the Gamma lines (the phase and absorption half
+  // spectra, packed as Z_k = P_k + i A_k).  The workgroup has at least
+  // 3 nr X / kEmax threads, so a thread owns at most 6 field and 3 Gamma
+  // elements.
+  {
+    constexpr int EF = 6, EG = 3;
+    const int nf = 2 * nr * X, ng = nr * X;
+    float2 vf[EF];
+    float4 vg[EG];
+#pragma unroll
+    for (int q = 0; q < EF; ++q) {
+      const int e = tid + q * nthr;
+      if (e < nf) {
+        const int t = e / X, i = e - t * X;
+        vf[q] = ((t & 1) ? b_src : a_src)[(row0 + (t >> 1)) * XC + ccol(i)];
+      }
     }
-    // packed line of the two half spectra: Z_k = P_k + i A_k (Hermitian extension)
-    int y = y0 + (t - 2 * nr), z = z0;
-    while (y >= Y) { y -= Y; ++z; }
-    const float2* gp = g_src + ((long)(z * 2 + 0) * Y + y) * Xh;
-    const float2* ga = g_src + ((long)(z * 2 + 1) * Y + y) * Xh;
-    const bool mirror = 2 * i > X;
-    const int kk = mirror ? X - i : i;
-    float2 P = gp[kk], A = ga[kk];
-    if (kk == 0 || 2 * kk == X) { P.y = 0.f; A.y = 0.f; }   // Re of the inverse ignores them
-    if (mirror) { P.y = -P.y; A.y = -A.y; }
-    return make_float2(P.x - A.y, P.y + A.x);
-  }, slot, [&] { wave0_sum(partials + v * tiles_x, tiles_x, &ibg_s); });   // sum S P^2
+#pragma unroll
+    for (int q = 0; q < EG; ++q) {
+      const int e = tid + q * nthr;
+      if (e < ng) {
+        const int r = e / X, i = e - r * X;
+        int y = y0 + r, z = z0;
+        while (y >= Y) { y -= Y; ++z; }
+        const int kk = 2 * i > X ? X - i : i;
+        const float2* gp = g_src + ((long)(z * 2 + 0) * Y + y) * Xh + kk;   // absorption: Y Xh on
+        const float2 P = gp[0], A = gp[(long)Y * Xh];
+        vg[q] = make_float4(P.x, P.y, A.x, A.y);
+      }
+    }
+    wave0_sum(partials + v * tiles_x, tiles_x, &ibg_s);   // sum S P^2
+#pragma unroll
+    for (int q = 0; q < EF; ++q) {
+      const int e = tid + q * nthr;
+      if (e < nf) {
+        const int t = e / X, i = e - t * X;
+        buf[t * LS + row_slot(i, PS)] = kept(i) ? vf[q] : make_float2(0.f, 0.f);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < EG; ++q) {
+      const int e = tid + q * nthr;
+      if (e < ng) {
+        const int r = e / X, i = e - r * X;
+        const bool mirror = 2 * i > X;
+        const int kk = mirror ? X - i : i;
+        float2 P = make_float2(vg[q].x, vg[q].y), A = make_float2(vg[q].z, vg[q].w);
+        if (kk == 0 || 2 * kk == X) { P.y = 0.f; A.y = 0.f; }   // Re of the inverse ignores them
+        if (mirror) { P.y = -P.y; A.y = -A.y; }
+        buf[(2 * nr + r) * LS + row_slot(i, PS)] = make_float2(P.x - A.y, P.y + A.x);
+      }
+    }
+  }
   __syncthreads();
   const float k = (float)(1.0 / ((double)X * (double)Y * ibg_s));
   double dsum = 0.0;
@@ -202,7 +244,7 @@ __global__ __launch_bounds__(1024) void k_tf_rows_bwd(const double* __restrict__
   if (tid == 0) dpart[v * wg_per_patch + wg] = tot;
   __syncthreads();
   auto store = [&](int t, int i, float2 val) {
-    ((t & 1) ? b_src : a_src)[(row0 + (t >> 1)) * X + i] = val;
+    if (kept(i)) ((t & 1) ? b_src : a_src)[(row0 + (t >> 1)) * XC + ccol(i)] = val;
   };
   if constexpr (NS > 0) {
     // last pass straight to memory
@@ -234,20 +276,23 @@ long bwd_wg_per_patch(const Sampling& sm) {
 }
 
 hipError_t launch_tf_rows_bwd(const double* partials, const Sampling& sm, int nv, float2* ab,
-                              const float2* g, double* dpart, hipStream_t s) {
+                              const float2* g, double* dpart, hipStream_t s, const LatSupport* sup) {
   if (3L * sm.nx > kMaxElems) return hipErrorInvalidValue;
+  const LatSupport ls = sup ? *sup : full_support(sm);
+  if (ls.xc < 1 || ls.xc > sm.nx || ls.kp < 0 || ls.kp >= ls.xc || ls.ly != sm.ny || ls.lx != sm.nx)
+    return hipErrorInvalidValue;
   FftPlan plan;
   if (!make_plan(sm.nx, &plan)) return hipErrorInvalidValue;
   const int R = bwd_rows_per_wg(sm);
   const long wpp = bwd_wg_per_patch(sm);
-  const long tiles_x = (sm.nx + tf_tile_width(sm) - 1) / tf_tile_width(sm);
+  const long tiles_x = pupil_tiles(sm, ls);
   const int thr = threads_for(3L * R * sm.nx);
   const size_t lds = (size_t)(sm.nx + 3L * R * row_stride(sm.nx)) * sizeof(float2);
   ScopedTiming _t("k_tf_rows_bwd", s);
 #define X_(NN)                                                                                   \
   case NN:                                                                                       \
     hipLaunchKernelGGL((k_tf_rows_bwd<NN>), dim3((unsigned)(wpp * nv)), dim3(thr), lds, s, partials, \
-                       tiles_x, sm, ab, g, dpart, R, wpp, plan);                               \
+                       tiles_x, sm, ab, g, dpart, R, wpp, ls.xc, ls.kp, plan);                 \
     return hipGetLastError();
   switch (sm.nx) {
     WO_LATERAL_SIZES(X_)
@@ -256,7 +301,7 @@ hipError_t launch_tf_rows_bwd(const double* partials, const Sampling& sm, int nv
   }
 #undef X_
   hipLaunchKernelGGL((k_tf_rows_bwd<0>), dim3((unsigned)(wpp * nv)), dim3(thr), lds, s, partials,
-                     tiles_x, sm, ab, g, dpart, R, wpp, plan);
+                     tiles_x, sm, ab, g, dpart, R, wpp, ls.xc, ls.kp, plan);
   return hipGetLastError();
 }
 
@@ -272,7 +317,8 @@ __global__ __launch_bounds__(1024) void k_tf_grad_y(const DevOptics* __restrict_
                                                     const float2* __restrict__ ab,
                                                     double* __restrict__ gpart,
                                                     double* __restrict__ ipart, int W,
-                                                    long tiles_x, int ZC, FftPlan plan) {
+                                                    long tiles_x, int ZC, int XC, int KP,
+                                                    FftPlan plan) {
   extern __shared__ float2 smem[];
   __shared__ double red[kMaxThreads / 64];
   constexpr int EPT = 2;   // lateral frequencies of a thread: Y * W <= 2 * threads
@@ -320,8 +366,9 @@ __global__ __launch_bounds__(1024) void k_tf_grad_y(const DevOptics* __restrict_
       const int e = tid + i * nthr;
       if (e >= Y * W) continue;
       const int ky = e >> wsh, w = e & (W - 1);
-      const int kx = x0 + w;
-      if (kx >= X) continue;
+      const int c = x0 + w;   // compact column of the fields
+      if (c >= XC) continue;
+      const int kx = field_column(c, KP, X, XC);
       const double fy = fftfreq(ky, Y, sm.dy), fx = fftfreq(kx, X, sm.dx);
       const double rp = sqrt(fy * fy + fx * fx);
       const double P = disc(fy, fx, rd, hw);
@@ -371,8 +418,8 @@ __global__ __launch_bounds__(1024) void k_tf_grad_y(const DevOptics* __restrict_
         const int ky = e >> (wsh + 1);
         const int r = e & (2 * W - 1);
         const int f = r >> wsh, w = r & (W - 1);
-        const int kx = x0 + w;
-        t[i] = kx < X ? ab[(((v * 2 + f) * Z + z) * (long)Y + ky) * X + kx] : make_float2(0.f, 0.f);
+        const int c = x0 + w;
+        t[i] = c < XC ? ab[(((v * 2 + f) * Z + z) * (long)Y + ky) * XC + c] : make_float2(0.f, 0.f);
       }
     }
   };
@@ -427,7 +474,7 @@ __global__ __launch_bounds__(1024) void k_tf_grad_y(const DevOptics* __restrict_
     for (int i = 0; i < EPT; ++i) {
       const int e = tid + i * nthr;
       if (e >= Y * W || Qe[i] == 0.0) continue;
-      const int ky = e >> wsh, kx = x0 + (e & (W - 1));
+      const int ky = e >> wsh, kx = field_column(x0 + (e & (W - 1)), KP, X, XC);
       double zj[7], dwdna;
       zernike_terms(o, fftfreq(ky, Y, sm.dy), fftfreq(kx, X, sm.dx), zj, &dwdna);
       g[1] -= tp * dwdna * Qe[i];
@@ -457,9 +504,14 @@ static int grad_threads(const Sampling& sm) {
   return (int)(t < 64 ? 64 : t);
 }
 
-long grad_tiles(const Sampling& sm) {
+long grad_tiles(const Sampling& sm, const LatSupport* sup) {
   const int W = grad_tile_width(sm);
-  return (sm.nx + W - 1) / W;
+  return ((sup ? sup->xc : sm.nx) + W - 1) / W;
+}
+
+long pupil_tiles(const Sampling& sm, const LatSupport& ls) {
+  const int W = tf_tile_width(sm, ls.ly);
+  return (ls.xc + W - 1) / W;
 }
 
 // z chunk of the gradient kernel (the reduction reads ceil(nz / chunk) * tiles
@@ -470,12 +522,14 @@ int grad_z_chunk(const Sampling& sm, int nv) {
 }
 
 hipError_t launch_tf_grad_y(const DevOptics* opt, const Sampling& sm, int nv, const float2* ab,
-                            double* gpart, double* ipart, hipStream_t s) {
+                            double* gpart, double* ipart, hipStream_t s, const LatSupport* sup) {
   FftPlan plan;
   if (!make_plan(sm.ny, &plan)) return hipErrorInvalidValue;
   if (sm.ny > 2048) return hipErrorInvalidValue;
+  const LatSupport ls = sup ? *sup : full_support(sm);
+  if (ls.xc < 1 || ls.xc > sm.nx || ls.kp < 0 || ls.kp >= ls.xc) return hipErrorInvalidValue;
   const int W = grad_tile_width(sm);
-  const long tiles = grad_tiles(sm);
+  const long tiles = grad_tiles(sm, &ls);
   const int ZC = grad_z_chunk(sm, nv);
   const long nwg = tiles * ((sm.nz + ZC - 1) / ZC) * (long)nv;
   const int thr = grad_threads(sm);
@@ -483,7 +537,7 @@ hipError_t launch_tf_grad_y(const DevOptics* opt, const Sampling& sm, int nv, co
   ScopedTiming _t("k_tf_grad_y", s);
 #define WO_GRAD(NN, AA)                                                                          \
   hipLaunchKernelGGL((k_tf_grad_y<NN, AA>), dim3((unsigned)nwg), dim3(thr), lds, s, opt, sm, ab, gpart, \
-                     ipart, W, tiles, ZC, plan)
+                     ipart, W, tiles, ZC, ls.xc, ls.kp, plan)
 #define X_(NN)                                                                                   \
   case NN:                                                                                       \
     if (sm.aberrated) WO_GRAD(NN, true); else WO_GRAD(NN, false);                                \
@@ -581,11 +635,13 @@ __global__ __launch_bounds__(256) void k_adam(DevOptics* __restrict__ opt,
 
 hipError_t launch_adam(DevOptics* opt, TuneState* st, const Sampling& sm, int nv,
                        const double* ppart, const double* lpart, const double* dpart,
-                       const double* gpart, const double* ipart, int update, hipStream_t s) {
-  const long tiles_x = (sm.nx + tf_tile_width(sm) - 1) / tf_tile_width(sm);
+                       const double* gpart, const double* ipart, int update, hipStream_t s,
+                       const LatSupport* sup) {
+  const LatSupport ls = sup ? *sup : full_support(sm);
+  const long tiles_x = pupil_tiles(sm, ls);
   { ScopedTiming _t("k_adam", s);
   const int ZC = grad_z_chunk(sm, nv);
-  const long gt = grad_tiles(sm);
+  const long gt = grad_tiles(sm, &ls);
   const long gn = (long)((sm.nz + ZC - 1) / ZC) * gt;
   hipLaunchKernelGGL(k_adam, dim3(nv), dim3(256), 0, s, opt, st, sm, ppart, tiles_x, gt, lpart,
                      loss_blocks(sm), dpart, bwd_wg_per_patch(sm), gpart, gn, ipart, update); }

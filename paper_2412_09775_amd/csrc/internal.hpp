@@ -197,19 +197,27 @@ hipError_t launch_tf_pol5_z(const DevOptics* opt, const Sampling& sm, int npatch
 hipError_t launch_set_tune(TuneState* dst, const TuneState* host, int n, hipStream_t s);
 long loss_blocks(const Sampling& sm);
 long bwd_wg_per_patch(const Sampling& sm);
-// Column tiles of the gradient kernel; its partials hold nz * tiles * 4 (at
-// most) and tiles * 4 doubles per virtual patch.
-long grad_tiles(const Sampling& sm);
+// Column tiles of the gradient kernel over the support's compact columns (all
+// columns: sup = NULL); its partials hold nz * tiles * 4 (at most) and
+// tiles * 4 doubles per virtual patch.
+long grad_tiles(const Sampling& sm, const LatSupport* sup = nullptr);
+// Column tiles of the field kernel over the support's compact columns: the
+// pupil-sum partials per patch.
+long pupil_tiles(const Sampling& sm, const LatSupport& ls);
 hipError_t launch_loss_grad(const DevOptics* opt, const TuneState* st, const Sampling& sm, int nv,
                             const float2* D, float2* bank, double* lpart, int data_div,
                             hipStream_t s);
+// The backward kernels and Adam take the fields' compact columns (sup; NULL:
+// every column), as the field kernel wrote them.
 hipError_t launch_tf_rows_bwd(const double* partials, const Sampling& sm, int nv, float2* ab,
-                              const float2* g, double* dpart, hipStream_t s);
+                              const float2* g, double* dpart, hipStream_t s,
+                              const LatSupport* sup = nullptr);
 hipError_t launch_tf_grad_y(const DevOptics* opt, const Sampling& sm, int nv, const float2* ab,
-                            double* gpart, double* ipart, hipStream_t s);
+                            double* gpart, double* ipart, hipStream_t s, const LatSupport* sup = nullptr);
 hipError_t launch_adam(DevOptics* opt, TuneState* st, const Sampling& sm, int nv,
                        const double* ppart, const double* lpart, const double* dpart,
-                       const double* gpart, const double* ipart, int update, hipStream_t s);
+                       const double* gpart, const double* ipart, int update, hipStream_t s,
+                       const LatSupport* sup = nullptr);
 // Per patch, the start with the lowest loss: its optics into ropt[i] and the
 // patch's eta into eta[i].
 hipError_t launch_pick_best(const DevOptics* opt, const TuneState* st, int starts, int npatch,

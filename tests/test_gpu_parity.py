@@ -267,37 +267,6 @@ def test_fluorescence_eta_zero_is_pseudo_inverse(gpu_lib, torch):
     assert np.linalg.norm((G - R)[band]) / np.linalg.norm(R[band]) < 1e-4
 
 
-@pytest.mark.parametrize("name", ["labelfree_3d", "labelfree_3d_short_transforms", "sectors9_band", "pol5",
-                                  "fluor_cfg1", "thin_batch3", "labelfree_3d_band_batch2"])
-def test_overlapped_synthesis_and_reconstruction_equals_the_two_calls(gpu_lib, torch, name):
-    """wo_transfer_function_reconstruct runs the same kernels (the data's forward
-    transforms on a second stream): bank and reconstruction bit for bit those of
-    wo_transfer_function then wo_reconstruct, and the reconstruction within the
-    oracle's tolerance."""
-    opts = CASES[name]
-    print(f"[case] tf+reconstruct overlapped {name}", flush=True)
-    banks = [oracle_bank(o) for o in opts]
-    C = banks[0].shape[0]
-    ds = []
-    for i, o in enumerate(opts):
-        f = specimen(o, 500 + i)
-        d = linear.forward(banks[i], f) + synth.gaussian_noise((C,) + banks[i].shape[2:], 1e-3, 600 + i)
-        ds.append(d.astype(np.float32))
-    d = torch.from_numpy(np.stack(ds)).cuda()
-    eta = eta_for(opts[0], banks[0])
-    tf2 = gpu_lib.transfer_function(opts)
-    f2 = gpu_lib.reconstruct(opts, tf2, d, eta)
-    for _ in range(2):   # the second call reuses the side stream
-        f1, tf1 = gpu_lib.transfer_function_reconstruct(opts, d, eta)
-        torch.cuda.synchronize()
-        assert torch.equal(tf1, tf2) and torch.equal(f1, f2)
-    got = f1.cpu().numpy()
-    for i, o in enumerate(opts):
-        err = rel_l2(got[i], linear.reconstruct(banks[i], ds[i], None, eta))
-        print(f"  patch {i}: rel L2 = {err:.3e}")
-        assert err < TOL_REC
-
-
 def band_slice(torch, full, sup, ny):
     """The band layout cut from a full-layout bank (n, C, P, Z, Y, Xh)."""
     nb, kt = sup["band_rows"], sup["tf_cols"]
