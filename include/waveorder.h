@@ -348,7 +348,8 @@ int wo_stitch_tiles(const float* tiles, int32_t ny_t, int32_t nx_t, int32_t P, i
 int wo_fft_tune(int32_t op, const wo_optics* o, int32_t n, const void* tf, const float* in, float* out,
                 double eta, int32_t reps, void* ws, size_t ws_bytes, void* stream);
 /* The table as text, one line "kind n m batch extra w threads plan" per entry
- * (kind: rows_r2c, rows_c2r, cols, zop, tf_rows); NUL-terminated, truncated to len;
+ * (kind: rows_r2c, rows_c2r, cols, zop, tf_rows, tf_fields -- the field kernel's
+ * planes per workgroup in w); NUL-terminated, truncated to len;
  * *needed (may be NULL) receives the full size including the NUL. */
 int wo_fft_plans_export(char* buf, size_t len, size_t* needed);
 /* Adds entries in the export format; all or none: WO_EINVAL if a line is

@@ -919,6 +919,13 @@ std::vector<FftChoice> fft_candidates(const FftKey& k) {
           const FftChoice c{w, t, pl};
           if (tf_rows_choice_ok(k.n, c)) add(c);
         }
+  } else if (k.kind == kFftTfFields) {
+    const int Z = k.extra / 10;
+    add(tf_fields_default(Z, k.m, k.batch));
+    for (int w : {1, 2, 3, 4, 6, 8, 12, 16, 24, 32, 48, 64, 96}) {
+      const FftChoice c{w, 0, 0};
+      if (tf_fields_choice_ok(Z, c)) add(c);
+    }
   } else if (k.kind == kFftZop) {
     const int P = (k.extra % 100000) / 1000, C = (k.extra / 10) % 100, mode = k.extra % 10;
     const int cin = mode == kModeForward ? P : C;

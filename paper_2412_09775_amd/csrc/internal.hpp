@@ -46,8 +46,9 @@ struct ScopedTiming {
 //
 // Launch schedule of one FFT pass for one problem shape, chosen by timing
 // (wo_fft_tune) or by the default heuristics when the table has no entry.
-enum FftKind { kFftRowsR2C = 0, kFftRowsC2R = 1, kFftCols = 2, kFftZop = 3, kFftTfRows = 4 };
-constexpr int kFftKinds = 5;
+enum FftKind { kFftRowsR2C = 0, kFftRowsC2R = 1, kFftCols = 2, kFftZop = 3, kFftTfRows = 4,
+               kFftTfFields = 5 };
+constexpr int kFftKinds = 6;
 // plan: 0 = the compiled stages of the length when there are some, else the
 // runtime plan in the default radix order; 1 = runtime plan, default order
 // (8, 4, 2, 3, 5); 2 = runtime plan, reversed pass order; 3 = runtime plan,
@@ -80,6 +81,12 @@ unsigned long long fft_table_version();
 // workgroup, two LDS lines each).
 bool tf_rows_choice_ok(int X, const FftChoice& c);
 FftChoice tf_rows_default(int X);
+// Schedules of the field kernel: w = planes per workgroup (the z-independent
+// pupil factors are evaluated once per workgroup), for Z planes, `tiles`
+// column tiles and `npatch` field sets (key: n = transform length, m = tiles,
+// batch = npatch, extra = Z * 10 + fields).
+bool tf_fields_choice_ok(int Z, const FftChoice& c);
+FftChoice tf_fields_default(int Z, long tiles, long npatch);
 // A workgroup of `thr` threads can own `elems` elements (kEmax per thread).
 inline bool threads_ok(int thr, long elems) {
   return thr >= 64 && thr <= kMaxThreads && thr % 64 == 0 && (long)thr * kEmax >= elems;

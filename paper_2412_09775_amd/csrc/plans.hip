@@ -31,6 +31,7 @@ const char* kind_name(int k) {
     case kFftCols: return "cols";
     case kFftZop: return "zop";
     case kFftTfRows: return "tf_rows";
+    case kFftTfFields: return "tf_fields";
     default: return "?";
   }
 }

@@ -351,6 +351,20 @@ int tf_z_chunk(const Sampling& sm, long tiles_x, long npatch, long target) {
   return (int)zc;
 }
 
+bool tf_fields_choice_ok(int Z, const FftChoice& c) {
+  return c.w >= 1 && c.w <= Z && c.threads == 0 && c.plan == 0;
+}
+
+// About 256 workgroups: each evaluates the z-independent pupil factors of its
+// tile once (FP64 square roots and divisions) and reuses them for up to 16
+// planes (96x512x512, 60 tiles: 93 us with 2 planes per workgroup, 70 us
+// with 16); the tuner picks the chunk by timing (12 planes: 58 us there).
+FftChoice tf_fields_default(int Z, long tiles, long npatch) {
+  Sampling sm{};
+  sm.nz = Z;
+  return FftChoice{tf_z_chunk(sm, tiles, npatch, 256), 0, 0};
+}
+
 // Column-tile width of the field kernel: at most 4096 elements (512 threads)
 // per workgroup.  The kernel synchronises its workgroup several times per
 // plane, so several smaller workgroups per CU hide those waits better than
@@ -380,11 +394,12 @@ hipError_t launch_tf_fields_y(const DevOptics* opt, const Sampling& sm, int npat
   const int nf = sm.model == kFluor3D ? 1 : 2;
   const int W = tf_tile_width(sm, LY);
   const long tiles = (ls.xc + W - 1) / W;
-  // about 256 workgroups: each evaluates the z-independent pupil factors of
-  // its tile once (FP64 square roots and divisions) and reuses them for up to
-  // 16 planes (96x512x512, 60 tiles: 93 us with 2 planes per workgroup, 70 us
-  // with 16)
-  const int ZC = tf_z_chunk(sm, tiles, npatch, 256);
+  const FftKey key{kFftTfFields, LY, tiles, (long)npatch, sm.nz * 10 + nf};
+  if (fft_recording())
+    fft_record(key, [=] { return launch_tf_fields_y(opt, sm, npatch, ab, partials, s, &ls); });
+  FftChoice fc;
+  if (!fft_lookup(key, &fc) || !tf_fields_choice_ok(sm.nz, fc)) fc = tf_fields_default(sm.nz, tiles, npatch);
+  const int ZC = fc.w;
   const long nwg = tiles * ((sm.nz + ZC - 1) / ZC) * (long)npatch;
   const int thr = threads_for((long)LY * nf * W);
   const size_t lds = (size_t)(LY + LY * nf * W) * sizeof(float2);

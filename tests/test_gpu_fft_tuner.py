@@ -108,3 +108,26 @@ def test_tuned_calls_match_oracle(gpu_lib, case):
     gpu_lib.fft_plans_import(table)
     assert gpu_lib.fft_plans_export() == table
     gpu_lib.fft_plans_clear()
+
+
+def test_every_field_kernel_chunk_gives_the_oracle_bank(gpu_lib, case):
+    """The TF synthesis records the field kernel's pass (planes per workgroup,
+    kind tf_fields); every candidate chunk gives the oracle's bank."""
+    import torch
+    o = case["o"]
+    gpu_lib.fft_plans_clear()
+    tfo = torch.empty_like(case["tf"])
+    gpu_lib.fft_tune(gpu_lib.OP_TRANSFER_FUNCTION, [o], out=tfo)
+    keys = [" ".join(ln.split()[:5]) for ln in gpu_lib.fft_plans_export().splitlines()]
+    fkeys = [k for k in keys if k.split()[0] == "tf_fields"]
+    assert len(fkeys) == 1, keys
+    ref = case["bank"][0][..., : o.nx // 2 + 1]
+    cands = gpu_lib.fft_candidates(fkeys[0])
+    print(f"[case] tf_fields {fkeys[0]}: {len(cands)} chunks", flush=True)
+    assert len(cands) >= 5
+    for line in cands:
+        gpu_lib.fft_plans_clear()
+        gpu_lib.fft_plans_import(line)
+        got = gpu_lib.transfer_function([o]).cpu().numpy()[0]
+        assert np.linalg.norm(got - ref) / np.linalg.norm(ref) < 1e-5, line
+    gpu_lib.fft_plans_clear()
