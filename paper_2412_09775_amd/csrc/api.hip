@@ -1172,9 +1172,6 @@ static int run_tf(const wo_optics* o, int32_t n, const Shape& s, void* tf_out, v
   // field buffer behind the compact fields.
   bool compact_out = false;
   LatSupport sup = tf_support(o, n, s, &compact_out);
-  // the band layout is the full one where the support fills the grid; else it
-  // comes from the compact Z pass of the label-free 3D models
-  if (band_out && !compact_out && (s.thin || sup.kt < s.Xh || sup.ky < s.Y)) return WO_EUNSUPPORTED;
   float2* tf = (float2*)tf_out;
   const long M = s.Y * s.Xh;
   const long plane = s.Y * s.Xh;
@@ -1254,6 +1251,11 @@ int wo_transfer_function_band(const wo_optics* o, int32_t n, void* tf_out, void*
   if (!tf_out || !ws) return WO_EINVAL;
   Shape s;
   bank_shape(o, &s);
+  // the band layout is the full one where the support fills the grid; else it
+  // comes from the compact Z pass of the label-free 3D models
+  bool compact_out = false;
+  const LatSupport sup = tf_support(o, n, s, &compact_out);
+  if (!compact_out && (s.thin || sup.kt < s.Xh || sup.ky < s.Y)) return WO_EUNSUPPORTED;
   if (ws_bytes < tf_ws(o, n, s)) return WO_ENOMEM;
   return run_tf(o, n, s, tf_out, ws, (hipStream_t)stream, true);
 }

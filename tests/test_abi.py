@@ -138,3 +138,29 @@ def test_tile_grid_host_logic_matches_the_oracle(lib):
         assert api.tile_grid(*args) == stitch.tile_grid(*args)
     with pytest.raises(api.WoError):
         api.tile_grid(100, 2, 200)          # tiles would not fit
+
+
+def test_support_and_band_calls_validate_on_the_host(lib):
+    """wo_lateral_support, wo_transfer_function_band and wo_linear_band reject bad
+    arguments before any GPU work (fake device pointers are never touched)."""
+    one = ctypes.c_void_p(1)
+    arr = api.optics_array(_optics())
+    assert lib.wo_lateral_support(arr, 1, None) == -1
+    assert lib.wo_lateral_support(api.optics_array(_optics(na_det=1.4)), 1, ctypes.byref(api.WoSupport())) == -1
+    # band synthesis: label-free 3D only (unless the support fills the grid)
+    thin = api.optics_array(_optics(model=api.MODEL_LABELFREE_THIN))
+    assert lib.wo_transfer_function_band(thin, 1, one, one, 1 << 40, None) == -2
+    pol5 = api.optics_array(_optics(model=api.MODEL_POL5_3D, na_det=0.75, ny=128, nx=128))
+    assert lib.wo_transfer_function_band(pol5, 1, one, one, 1 << 40, None) == -2
+    assert lib.wo_transfer_function_band(arr, 1, None, one, 1 << 40, None) == -1
+    assert lib.wo_transfer_function_band(arr, 1, one, one, 16, None) == -3
+    # band linear calls: forward, reconstruction or adjoint of a 3D model
+    assert lib.wo_linear_band(api.OP_TRANSFER_FUNCTION, arr, 1, one, one, None, 1e-3, one, one, 1 << 40,
+                              None) == -1
+    assert lib.wo_linear_band(api.OP_RECONSTRUCT, thin, 1, one, one, None, 1e-3, one, one, 1 << 40,
+                              None) == -2
+    assert lib.wo_linear_band(api.OP_RECONSTRUCT, arr, 1, one, one, None, -1.0, one, one, 1 << 40,
+                              None) == -1
+    assert lib.wo_linear_band(api.OP_RECONSTRUCT, arr, 1, one, one, None, 0.0, one, one, 1 << 40,
+                              None) == -2
+    assert lib.wo_linear_band(api.OP_ADJOINT, arr, 1, one, one, None, 0.0, one, one, 16, None) == -3
