@@ -70,13 +70,13 @@ void timing_begin(const char* name, hipStream_t s, void** token) {
     *token = nullptr;
     return;
   }
-  hipEventRecord(r->a, s);
+  (void)hipEventRecord(r->a, s);   // instrumentation: a failed record only loses the sample
   *token = r;
 }
 
 void timing_end(void* token, hipStream_t s) {
   TimingRec* r = (TimingRec*)token;
-  hipEventRecord(r->b, s);
+  (void)hipEventRecord(r->b, s);
   std::lock_guard<std::mutex> lk(g_tmu);
   g_recs.push_back(*r);
   delete r;
@@ -558,7 +558,7 @@ std::vector<TuneGroup> tune_groups(const wo_optics* o, int32_t n, int32_t starts
   for (int i = 0; i < n; ++i) {
     size_t k = 0;
     while (k < g.size() && !same_sampling(g[k].rep, &o[i])) ++k;
-    if (k == g.size()) g.push_back(TuneGroup{&o[i], {}, TuneLayout{}, 0, 0.0});
+    if (k == g.size()) g.push_back(TuneGroup{&o[i], {}, TuneLayout{}, 0, 0.0, 0, LatSupport{}});
     g[k].idx.push_back(i);
     if (aberrated(o[i])) g[k].ab = 1;
   }
@@ -834,7 +834,7 @@ hipGraphExec_t graph_cache_find(const std::string& key) {
 
 void graph_cache_insert(const std::string& key, hipGraphExec_t exec) {
   if (g_graphs.size() >= kGraphCache) {
-    hipGraphExecDestroy(g_graphs.front().second);
+    (void)hipGraphExecDestroy(g_graphs.front().second);
     g_graphs.erase(g_graphs.begin());
   }
   g_graphs.push_back({key, exec});
@@ -976,11 +976,11 @@ int run_tune(wo_optics* o, int32_t n, const float* d, const double* eta,
       ce = hipStreamEndCapture(cs->cap, &graph);
       if (was_timing) wo_timing_enable(1);
       if (ist || fe != hipSuccess || ce != hipSuccess) {
-        if (graph) hipGraphDestroy(graph);
+        if (graph) (void)hipGraphDestroy(graph);
         return ist ? ist : WO_EHIP;
       }
       const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-      hipGraphDestroy(graph);
+      (void)hipGraphDestroy(graph);
       if (ie != hipSuccess) return WO_EHIP;
       graph_cache_insert(key, exec);
     }

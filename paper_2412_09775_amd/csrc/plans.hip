@@ -171,8 +171,8 @@ int wo_fft_tune(int32_t op, const wo_optics* o, int32_t n, const void* tf, const
     }
     fft_store(key, best >= 0 ? cand[best] : cand[0]);
   }
-  if (a) hipEventDestroy(a);
-  if (b) hipEventDestroy(b);
+  if (a) (void)hipEventDestroy(a);
+  if (b) (void)hipEventDestroy(b);
   if (was_timing) wo_timing_enable(1);
   if (status == WO_OK && hipStreamSynchronize(hs) != hipSuccess) status = WO_EHIP;
   return status;
