@@ -766,36 +766,53 @@ __device__ __forceinline__ void line_of(int j, int nl, int nb, int shift, int& l
   }
 }
 
-template <int N, int NL, bool LF, int EM, bool PD, bool REV, typename LD, typename FIN, typename MID>
-__device__ __forceinline__ void first_pass_in2(float2* lds, int nl_rt, int es, int ls, int shift,
-                                               float s, int tid, int nthr, LD load, FIN finish,
-                                               MID mid) {
-  using PL = OrderedPlan<N, REV>;
-  constexpr int R0 = PL::radix(0), NB0 = N / R0;
-  constexpr int B0 = (EM + R0 - 1) / R0;
-  using T = decltype(load(0, 0));
+// The loaded inputs of a thread's first-pass butterflies (B0 butterflies of
+// radix R0), held between first_pass_load and first_pass_store.
+template <int N, int EM, bool REV, typename T = float2>
+struct FirstPassRaw {
+  static constexpr int R0 = OrderedPlan<N, REV>::radix(0);
+  static constexpr int B0 = (EM + R0 - 1) / R0;
+  T v[B0][R0];
+};
+
+// Issues every load of the thread's first-pass butterflies (load(l, i) as in
+// first_pass_in2).
+template <int N, int NL, bool LF, int EM, bool PD, bool REV, typename T, typename LD>
+__device__ __forceinline__ void first_pass_load(FirstPassRaw<N, EM, REV, T>& raw, int nl_rt, int shift,
+                                                int tid, int nthr, LD load) {
+  using FR = FirstPassRaw<N, EM, REV, T>;
+  constexpr int NB0 = N / FR::R0;
   const int nl = NL > 0 ? NL : nl_rt;
-  T raw[B0][R0];
 #pragma unroll
-  for (int b = 0; b < B0; ++b) {
+  for (int b = 0; b < FR::B0; ++b) {
     const int j = tid + b * nthr;
     if (j < nl * NB0) {
       int l, k;
       line_of<N, NL, LF, PD>(j, nl, NB0, shift, l, k);
 #pragma unroll
-      for (int r = 0; r < R0; ++r) raw[b][r] = load(l, k + r * NB0);
+      for (int r = 0; r < FR::R0; ++r) raw.v[b][r] = load(l, k + r * NB0);
     }
   }
-  mid();
+}
+
+// The first pass on loaded inputs (finish(l, i, v) applied to each) into LDS;
+// ends with a barrier.
+template <int N, int NL, bool LF, int EM, bool PD, bool REV, typename T, typename FIN>
+__device__ __forceinline__ void first_pass_store(const FirstPassRaw<N, EM, REV, T>& raw, float2* lds,
+                                                 int nl_rt, int es, int ls, int shift, float s, int tid,
+                                                 int nthr, FIN finish) {
+  using FR = FirstPassRaw<N, EM, REV, T>;
+  constexpr int R0 = FR::R0, NB0 = N / R0;
+  const int nl = NL > 0 ? NL : nl_rt;
 #pragma unroll
-  for (int b = 0; b < B0; ++b) {
+  for (int b = 0; b < FR::B0; ++b) {
     const int j = tid + b * nthr;
     if (j < nl * NB0) {
       int l, k;
       line_of<N, NL, LF, PD>(j, nl, NB0, shift, l, k);
       float2 v[R0];
 #pragma unroll
-      for (int r = 0; r < R0; ++r) v[r] = finish(l, k + r * NB0, raw[b][r]);
+      for (int r = 0; r < R0; ++r) v[r] = finish(l, k + r * NB0, raw.v[b][r]);
       dft_small<R0>(v, s);
 #pragma unroll
       for (int r = 0; r < R0; ++r)
@@ -803,6 +820,16 @@ __device__ __forceinline__ void first_pass_in2(float2* lds, int nl_rt, int es, i
     }
   }
   __syncthreads();
+}
+
+template <int N, int NL, bool LF, int EM, bool PD, bool REV, typename LD, typename FIN, typename MID>
+__device__ __forceinline__ void first_pass_in2(float2* lds, int nl_rt, int es, int ls, int shift,
+                                               float s, int tid, int nthr, LD load, FIN finish,
+                                               MID mid) {
+  FirstPassRaw<N, EM, REV, decltype(load(0, 0))> raw;
+  first_pass_load<N, NL, LF, EM, PD, REV>(raw, nl_rt, shift, tid, nthr, load);
+  mid();
+  first_pass_store<N, NL, LF, EM, PD, REV>(raw, lds, nl_rt, es, ls, shift, s, tid, nthr, finish);
 }
 
 // As first_pass_in2 with the loaded values used as they are.

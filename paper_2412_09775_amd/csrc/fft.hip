@@ -276,9 +276,10 @@ __device__ __forceinline__ bool in_band(int y, int ky, int nb, int Y) {
 }
 
 // band: 0 every row; 1 stores only the band rows (ky, nb) of the transform;
-// 2 loads only the band rows (the others are taken as zero).
+// 2 loads only the band rows (the others are taken as zero).  At most 64
+// VGPRs (8 waves per SIMD), so that two 1024-thread workgroups share a CU.
 template <int NS, int WS>
-__global__ __launch_bounds__(1024) void k_cols(float2* __restrict__ data, int N, long M, int Wrt,
+__global__ __launch_bounds__(1024, 8) void k_cols(float2* __restrict__ data, int N, long M, int Wrt,
                                                long tiles_m, long planes_per_group,
                                                long group_stride, FftPlan plan, float sign,
                                                int band, int ky, int nb) {
@@ -322,6 +323,62 @@ __global__ __launch_bounds__(1024) void k_cols(float2* __restrict__ data, int N,
   }
 }
 
+// k_cols for a compiled length and tile width as a loop over tiles: workgroup
+// g of G transforms tiles g, g + G, ... and issues the loads of its next tile
+// right after the first pass of the current one, so that they are in flight
+// during its remaining passes and stores.
+template <int NS, int WS>
+__global__ __launch_bounds__(1024) void k_cols_loop(float2* __restrict__ data, long M, long tiles_m,
+                                                    long planes_per_group, long group_stride,
+                                                    long total, float sign, int band, int ky,
+                                                    int nb) {
+  static_assert(NS > 0 && WS > 0, "compiled length and tile width");
+  constexpr int W = WS;
+  constexpr int NP = StaticPlan<NS>::passes();
+  const int wsh = pow2_shift(WS);
+  extern __shared__ float2 smem[];
+  float2* tw = smem;
+  float2* buf = smem + NS;
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const long G = gridDim.x;
+  auto tile_at = [&](long t, long& m0, int& weff) {
+    const long tile = t % tiles_m, plane = t / tiles_m;
+    const long pg = plane / planes_per_group, pi = plane - pg * planes_per_group;
+    m0 = tile * W;
+    weff = (int)min((long)W, M - m0);
+    return data + (pg * group_stride + pi) * (long)NS * M;
+  };
+  auto issue = [&](FirstPassRaw<NS, kEmax, false>& raw, long t) {
+    long m0;
+    int weff;
+    const float2* base = tile_at(t, m0, weff);
+    first_pass_load<NS, WS, true, kEmax, false, false>(raw, W, wsh, tid, nthr, [&](int l, int n) {
+      return l < weff && (band != 2 || in_band(n, ky, nb, NS)) ? base[(long)n * M + m0 + l]
+                                                               : make_float2(0.f, 0.f);
+    });
+  };
+  FirstPassRaw<NS, kEmax, false> raw;
+  long t = xcd_block();   // G <= total: every workgroup has a first tile
+  issue(raw, t);
+  fill_twiddles(tw, NS, tid, nthr);
+  while (t < total) {
+    long m0;
+    int weff;
+    float2* base = tile_at(t, m0, weff);
+    first_pass_store<NS, WS, true, kEmax, false, false>(raw, buf, W, W, 1, wsh, sign, tid, nthr,
+                                                        [](int, int, float2 v) { return v; });
+    const long tn = t + G;
+    if (tn < total) issue(raw, tn);
+    static_passes<NS, WS, true, kEmax, false, false, 1, NP - 1>(buf, W, W, 1, wsh, tw, sign, tid, nthr);
+    last_pass_out<NS, WS, true, kEmax, false, false>(buf, W, W, 1, wsh, tw, sign, tid, nthr,
+                                                     [&](int l, int n, float2 v) {
+                                                       if (l < weff && (band != 1 || in_band(n, ky, nb, NS)))
+                                                         base[(long)n * M + m0 + l] = v;
+                                                     });
+    t = tn;
+  }
+}
+
 // Column tile width: W contiguous complex values per row (W = 16 is one
 // 128-byte segment), limited by the elements a workgroup may own and by the
 // device's LDS per workgroup (twiddles + tile).
@@ -340,10 +397,27 @@ constexpr int static_tile_width(int n) {
   return W;
 }
 
+// Schedule plan 4: the compiled transform with the compiled tile width, as the
+// tile loop k_cols_loop.
+constexpr int kPlanColsLoop = 4;
+
 static bool cols_choice_ok(int N, const FftChoice& c) {
   const long elems = (long)c.w * N;
+  const bool loop_ok = c.plan == kPlanColsLoop && compiled_length(N) && c.w == static_tile_width(N);
   return pow2_shift(c.w) >= 0 && c.w <= 64 && elems <= kMaxElems && threads_ok(c.threads, elems) &&
-         (long)(N + elems) * (long)sizeof(float2) <= lds_limit_bytes() && c.plan >= 0 && c.plan <= 3;
+         (long)(N + elems) * (long)sizeof(float2) <= lds_limit_bytes() && c.plan >= 0 &&
+         (c.plan <= 3 || loop_ok);
+}
+
+// Workgroups of a tile loop: as many as are resident on the device at once
+// (all of them when the occupancy query fails), at most one per tile.
+static long loop_grid(const void* fn, int thr, size_t lds, long total) {
+  int dev = 0, cus = 0, per = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, thr, lds) != hipSuccess || per < 1 || cus < 1)
+    return total;
+  return std::min(total, (long)per * cus);
 }
 
 static FftChoice cols_default(int N) {
@@ -375,7 +449,12 @@ hipError_t launch_cols(float2* data, int N, long M, long planes_per_group, long 
   ScopedTiming _t(tag, s);
 #define X_(NN)                                                                                  \
   case NN:                                                                                      \
-    if (W == static_tile_width(NN))                                                             \
+    if (c.plan == kPlanColsLoop) {                                                              \
+      const void* fn = reinterpret_cast<const void*>(&k_cols_loop<NN, static_tile_width(NN)>);  \
+      const long g = loop_grid(fn, thr, lds, nwg);                                              \
+      hipLaunchKernelGGL((k_cols_loop<NN, static_tile_width(NN)>), dim3((unsigned)g), dim3(thr), lds, \
+                         s, data, M, tiles, planes_per_group, group_stride, nwg, sign, band, ky, nb); \
+    } else if (W == static_tile_width(NN))                                                      \
       hipLaunchKernelGGL((k_cols<NN, static_tile_width(NN)>), dim3((unsigned)nwg), dim3(thr), lds, \
                          s, data, N, M, W, tiles, planes_per_group, group_stride, plan, sign, band, \
                          ky, nb);                                                               \
@@ -383,7 +462,7 @@ hipError_t launch_cols(float2* data, int N, long M, long planes_per_group, long 
       hipLaunchKernelGGL((k_cols<NN, 0>), dim3((unsigned)nwg), dim3(thr), lds, s, data, N, M, W, \
                          tiles, planes_per_group, group_stride, plan, sign, band, ky, nb);      \
     return hipGetLastError();
-  if (c.plan == 0) switch (N) {
+  if (c.plan == 0 || c.plan == kPlanColsLoop) switch (N) {
       WO_ALL_SIZES(X_)
       default:
         break;
@@ -910,6 +989,10 @@ std::vector<FftChoice> fft_candidates(const FftKey& k) {
           const FftChoice c{w, t, pl};
           if (cols_choice_ok(k.n, c)) add(c);
         }
+    for (int t : thread_options((long)static_tile_width(k.n) * k.n)) {
+      const FftChoice c{static_tile_width(k.n), t, kPlanColsLoop};
+      if (cols_choice_ok(k.n, c)) add(c);
+    }
   } else if (k.kind == kFftTfRows) {
     const FftChoice d = tf_rows_default(k.n);
     add(d);

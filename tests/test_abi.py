@@ -114,16 +114,21 @@ def test_fft_schedule_table_host_logic(lib):
             f = ln.split()
             assert " ".join(f[:5]) == key
             w, thr, plan = map(int, f[5:])
-            assert 64 <= thr <= 1024 and thr % 64 == 0 and 0 <= plan <= 3 and w >= 1
+            assert 64 <= thr <= 1024 and thr % 64 == 0 and w >= 1
+            # plan 4: the column tile loop, compiled lengths at the compiled width only
+            assert 0 <= plan <= 3 or (plan == 4 and key.startswith("cols 96 ") and w == 16)
     # 80 = 8*2*5 has three distinct radix orders; 96 = 8*4*3 also; 24 = 8*3 two
     assert {int(ln.split()[-1]) for ln in api.fft_candidates("rows_r2c 80 0 2304 0")} == {0, 2, 3}
     assert {int(ln.split()[-1]) for ln in api.fft_candidates("zop 24 3936 1 2011")} == {0, 2}
+    assert 4 in {int(ln.split()[-1]) for ln in api.fft_candidates("cols 96 41 48 0")}
     pick = api.fft_candidates("cols 96 41 48 0")[-1]
     api.fft_plans_import(pick)
     assert api.fft_plans_export() == pick + "\n"
     for bad in ("cols 96 41 48 0 64 64 0",       # 64 x 96 elements need 768 threads or more
                 "cols 96 41 48 0 1 100 0",       # not a multiple of 64
                 "zop 24 3936 1 2011 1 64 7",     # no such plan
+                "zop 24 3936 1 2011 1 64 4",     # the tile loop is a column schedule
+                "cols 96 41 48 0 8 192 4",       # the tile loop runs the compiled width only
                 "nonsense 1 2 3"):
         with pytest.raises(api.WoError):
             api.fft_plans_import(bad)

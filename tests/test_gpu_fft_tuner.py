@@ -131,3 +131,44 @@ def test_every_field_kernel_chunk_gives_the_oracle_bank(gpu_lib, case):
         got = gpu_lib.transfer_function([o]).cpu().numpy()[0]
         assert np.linalg.norm(got - ref) / np.linalg.norm(ref) < 1e-5, line
     gpu_lib.fft_plans_clear()
+
+
+def test_column_tile_loop_over_several_tiles_per_workgroup(gpu_lib):
+    """Schedule plan 4 of the column passes: a resident grid of workgroups that
+    each transform several tiles in turn (the loads of the next tile in flight
+    during the passes of the current one).  At 32×512×576 the 512-point Y
+    passes cover more 16-column tiles than the device holds workgroups of 1024
+    threads at once; reconstruction and forward model against the oracle."""
+    import torch
+    o = labelfree(nz=32, ny=512, nx=576)
+    bank = tfm.transfer_function(o)
+    f = synth.ellipsoids((o.nz, o.ny, o.nx), (o.dz, o.dy, o.dx), 24, seed=93)
+    d = linear.forward(bank, f) + synth.gaussian_noise((1, o.nz, o.ny, o.nx), 1e-3, 94)
+    eta = 1e-3 * linear.max_singular_value_sq(bank)
+    tf = gpu_lib.transfer_function([o])
+    dd = torch.from_numpy(d[None].astype(np.float32)).cuda()
+    ff = torch.from_numpy(f[None].astype(np.float32)).cuda()
+    lines = []
+    for op_, x, shape in ((gpu_lib.OP_RECONSTRUCT, dd, (1, 2)), (gpu_lib.OP_FORWARD, ff, (1, 1))):
+        gpu_lib.fft_plans_clear()
+        out = torch.empty(shape + (o.nz, o.ny, o.nx), device="cuda")
+        gpu_lib.fft_tune(op_, [o], tf=tf, x=x, out=out, eta=eta)
+        for ln in gpu_lib.fft_plans_export().splitlines():
+            key = " ".join(ln.split()[:5])
+            if key.startswith("cols 512 "):
+                loop = [c for c in gpu_lib.fft_candidates(key) if c.split()[-1] == "4"]
+                assert loop, key
+                lines.append(loop[0])
+    gpu_lib.fft_plans_clear()
+    assert len(lines) >= 2
+    print(f"[case] tile-loop schedules: {lines}", flush=True)
+    gpu_lib.fft_plans_import("\n".join(lines))
+    try:
+        got = gpu_lib.reconstruct([o], tf, dd, eta)[0].cpu().numpy()
+        e_rec = rel(got, linear.reconstruct(bank, d, eta=eta))
+        got = gpu_lib.forward([o], tf, ff)[0].cpu().numpy()
+        e_fwd = rel(got, linear.forward(bank, f))
+    finally:
+        gpu_lib.fft_plans_clear()
+    print(f"  rel reconstruct {e_rec:.2e} forward {e_fwd:.2e}")
+    assert e_rec < 1e-4 and e_fwd < 1e-5
