@@ -329,7 +329,8 @@ int wo_stitch_tiles(const float* tiles, int32_t ny_t, int32_t nx_t, int32_t P, i
  * transform) -- is launched with a schedule: the lines, rows or columns
  * one workgroup transforms, the workgroup size, and the radix plan (compiled
  * stages for the compiled lengths, else a runtime plan in one of three radix
- * orders).  Without tuning each pass takes a fixed heuristic schedule; a
+ * orders; plan 4, for the column passes at a compiled length and width, is a
+ * resident grid whose workgroups loop over the tiles).  Without tuning each pass takes a fixed heuristic schedule; a
  * process-wide table keyed by (pass, length, columns, batch[, P, C, mode])
  * overrides it.  Tuning or importing changes launch schedules only: results
  * are the same transform up to FP32 rounding.  The table is guarded by a
