@@ -698,8 +698,10 @@ struct ZopGeom {
   int R, ky, nb, tiles_row, bank_band;
 };
 
+// With compiled stages at most 72 VGPRs (7 waves per SIMD, no spills); the
+// runtime-plan instances keep their allocation (they would spill).
 template <int P, int CT, int NS>
-__global__ __launch_bounds__(1024) void k_zop(float2* __restrict__ spec,
+__global__ __launch_bounds__(1024, NS > 0 ? 7 : 1) void k_zop(float2* __restrict__ spec,
                                               const float2* __restrict__ tf, int C, int Z, ZopGeom gm,
                                               int slots, int W, long tiles_m, FftPlan plan,
                                               int mode, float eta, const float* __restrict__ bg,
