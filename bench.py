@@ -313,8 +313,8 @@ def main():
         torch.cuda.synchronize()
         tuner["ms_per_step_default_schedules"] = (time.perf_counter() - a) * 1e3 / args.steps
         a = time.perf_counter()
-        api.fft_tune(api.OP_TRANSFER_FUNCTION, [o], out=tf_buf, reps=5, ws=ws_tf, stream=stream)
-        api.fft_tune(api.OP_RECONSTRUCT, [o], tf=tf_buf, x=d, out=fout, eta=eta, reps=5, ws=ws_rec,
+        api.fft_tune(api.OP_TRANSFER_FUNCTION, [o], out=tf_buf, reps=15, ws=ws_tf, stream=stream)
+        api.fft_tune(api.OP_RECONSTRUCT, [o], tf=tf_buf, x=d, out=fout, eta=eta, reps=15, ws=ws_rec,
                      stream=stream)
         tuner["tune_s"] = round(time.perf_counter() - a, 3)
         for _ in range(args.warmup):
