@@ -232,3 +232,11 @@ def labelfree_3d_at(o: op.Optics, kz: int, ky: int, kx: int):
     hp = np.sum(ez * (cp + np.conj(cm)))
     ha = np.sum(ez * 1j * (cp - np.conj(cm)))
     return hp, ha
+
+
+def pol5_3d_at(o: op.Optics, kz: int, ky: int, kx: int) -> np.ndarray:
+    """(5, 4) polarisation bank at one frequency index: pol5_3d's composition applied
+    to labelfree_3d_at (the direct source sum, no FFT)."""
+    hp, ha = labelfree_3d_at(o, kz, ky, kx)
+    k = pol5_coupling(o.swing)
+    return k.real * hp + k.imag * ha

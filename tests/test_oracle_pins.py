@@ -362,6 +362,91 @@ def test_pol5_background():
     assert np.allclose(bg[1:], math.sin(math.pi * 0.1) ** 2)
 
 
+def jones_abbe_channel_response(o, e, a, B, eps=1e-3):
+    """First-order channel response of a weak point scatterer with Jones
+    perturbation eps * B at the origin, by brute force over source points:
+    I(eps) = sum_q S(q) |a^H (e d_q + eps B e s)|^2 with the direct plane wave
+    d_q = P(q) E(q) exp(i 2 pi (q.x + kz(q)(z - dz0))) carrying the illumination
+    state e through the pupil, and the scattered field
+    s = (1 / (Y X)) sum_p P(p) E(p) g(p) exp(i 2 pi (p.x + kz(p)(z - dz0)))
+    carrying B e; returns (I(eps) - I(-eps)) / (2 eps I_bg) on the (Z, Y, X) grid
+    (exact: I is quadratic in eps).  Jones vectors throughout; the
+    kappa-composition of the bank is not used."""
+    S = op.illumination_pupil(o)
+    P = op.detection_pupil(o)
+    E = op.aberration(o)
+    fy, fx = op.lateral_frequencies(o)
+    kz = op.axial_wavenumber(o)
+    ys = np.arange(o.ny)[:, None] * o.dy
+    xs = np.arange(o.nx)[None, :] * o.dx
+    ibg = np.sum(S * P * P)
+    g = np.where(P > 0, 1j * o.k_medium / np.where(kz > 0, kz, 1.0), 0.0)
+    pidx = np.argwhere(P > 0)
+    ah = np.conj(a)
+    out = np.zeros((o.nz, o.ny, o.nx))
+    for zi, z in enumerate(op.z_planes_3d(o)):
+        s = np.zeros((o.ny, o.nx), dtype=np.complex128)
+        for p in map(tuple, pidx):
+            s += P[p] * E[p] * g[p] * np.exp(2j * np.pi * (fy[p] * ys + fx[p] * xs + kz[p] * (z - o.defocus)))
+        s /= o.ny * o.nx
+        scat = B @ e                                   # Jones vector of the scattered wave
+        for q in map(tuple, np.argwhere(S * P > 0)):
+            d = P[q] * E[q] * np.exp(2j * np.pi * (fy[q] * ys + fx[q] * xs + kz[q] * (z - o.defocus)))
+            inten = []
+            for sg in (eps, -eps):
+                field = [e[j] * d + sg * scat[j] * s for j in range(2)]     # (Ex, Ey) on the grid
+                inten.append(np.abs(ah[0] * field[0] + ah[1] * field[1]) ** 2)
+            out[zi] += S[q] * (inten[0] - inten[1]) / (2 * eps)
+    return out / ibg
+
+
+def test_pol5_bank_is_the_jones_abbe_response_of_a_weak_point_scatterer():
+    """The 5 x 4 bank against the brute-force channel intensities of a point scatterer
+    with each property's Jones perturbation (Table 1 vector row, paraxial reading R9):
+    FFT3 of the first-order response of channel c to property p equals H_cp.  A sign
+    slip on the Im(kappa) term or swapped phase/absorption columns fails here."""
+    o = lf_optics(model=op.POL5_3D, nz=3, ny=8, nx=8, dx=0.13, dy=0.13, na_det=0.8, na_ill=0.45,
+                  defocus=0.15, tilt_zenith=0.2, tilt_azimuth=0.7, swing=0.1)
+    bank = tfm.pol5_3d(o)
+    states, a = tfm.pol5_states(o.swing)
+    Bs = tfm.pol5_property_matrices()
+    scale = np.abs(bank).max()
+    for c, e in enumerate(states):
+        for p, B in enumerate(Bs):
+            ref = np.fft.fftn(jones_abbe_channel_response(o, e, a, B))
+            assert np.max(np.abs(bank[c, p] - ref)) < 1e-10 * scale, (c, p)
+    # the flipped compositions are far off (what this test guards against)
+    hp, ha = tfm.labelfree_3d(o)
+    k = tfm.pol5_coupling(o.swing)
+    ref = np.fft.fftn(jones_abbe_channel_response(o, states[1], a, Bs[1]))
+    for wrong in (k[1, 1].real * hp - k[1, 1].imag * ha, k[1, 1].real * ha + k[1, 1].imag * hp):
+        assert np.max(np.abs(wrong - ref)) > 1e-3 * scale
+
+
+def test_pol5_bank_at_one_frequency_is_the_bank():
+    """The one-frequency polarisation bank (direct source sum) equals pol5_3d there."""
+    o = lf_optics(model=op.POL5_3D, nz=4, ny=8, nx=10, dx=0.13, dy=0.13, na_det=0.8, na_ill=0.45,
+                  defocus=0.1, tilt_zenith=0.15, swing=0.08)
+    bank = tfm.pol5_3d(o)
+    for k in [(0, 0, 0), (1, 2, 3), (3, 7, 9), (2, 5, 1)]:
+        assert np.allclose(tfm.pol5_3d_at(o, *k), bank[(slice(None), slice(None)) + k],
+                           atol=1e-12 * np.abs(bank).max())
+
+
+def test_jones_abbe_response_reduces_to_the_scalar_phase_response():
+    """Scalar limit of the brute force: an analyser that passes the illumination
+    state entirely and an isotropic perturbation (B = I, B = i I) give the scalar
+    label-free phase and absorption point responses 2 Re c and -2 Im c."""
+    o = lf_optics(nz=3, ny=8, nx=8, dx=0.13, dy=0.13, na_det=0.8, na_ill=0.45, defocus=0.15,
+                  tilt_zenith=0.2, tilt_azimuth=0.7)
+    c = abbe_point_response(o)
+    e = np.array([1.0, 1.0j]) / math.sqrt(2.0)
+    ph = jones_abbe_channel_response(o, e, e, np.eye(2))
+    ab = jones_abbe_channel_response(o, e, e, 1j * np.eye(2))
+    assert np.allclose(ph, 2 * c.real, atol=1e-11 * np.abs(c).max())
+    assert np.allclose(ab, -2 * c.imag, atol=1e-11 * np.abs(c).max())
+
+
 # ---------------------------------------------------------------- auto-tune pieces
 
 def test_analytic_gradient_matches_finite_differences():
