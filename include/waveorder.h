@@ -180,22 +180,46 @@ int wo_reconstruct(const wo_optics* o, int32_t n, const void* tf, const float* d
  * k < tf_cols of the half spectrum; every other value of the full bank is zero
  * and implied, as the Hermitian half is.  The values are those
  * wo_transfer_function writes there, bit for bit.  Label-free 3D models
- * (one or nine apertures), or any 3D model whose support fills the grid (then
- * the layout is the full one); others: WO_EUNSUPPORTED.  Workspace as for
- * wo_transfer_function. */
+ * (one or nine apertures), the polarisation model, or any 3D model whose
+ * support fills the grid (then the layout is the full one); others:
+ * WO_EUNSUPPORTED.  Workspace as for wo_transfer_function.
+ *
+ * POL5_3D is stored in reduced form: its 5 x 4 bank is a constant mix of the
+ * label-free pair, H_cp = Re(kappa_cp) H_phase + Im(kappa_cp) H_abs (the
+ * paraxial Jones reduction of Table 1's vector row; kappa from
+ * wo_pol5_coupling), so the band layout holds only that pair,
+ * [n][2][nz][band_rows][tf_cols] (H_phase, H_abs), a tenth of the entries.
+ * wo_transfer_function's full bank is exactly its expansion: on the support
+ * each entry is Re(kappa) * H_phase + Im(kappa) * H_abs evaluated in FP32 with
+ * every product and the sum rounded on their own (no fused multiply-add),
+ * zero elsewhere. */
 int wo_transfer_function_band(const wo_optics* o, int32_t n, void* tf_out, void* ws, size_t ws_bytes,
                               void* stream);
 /* wo_forward (op WO_OP_FORWARD: in = f, out = d, eta ignored), wo_reconstruct
  * (WO_OP_RECONSTRUCT: in = d, out = f) or wo_adjoint (WO_OP_ADJOINT: in = r,
  * out = g, b ignored) with the bank in the band layout of
- * wo_transfer_function_band; results bit for bit those of the full-layout
- * call.  3D models only (thin: WO_EUNSUPPORTED); workspace as for those calls. */
+ * wo_transfer_function_band (POL5_3D: the reduced form, whose entries the
+ * fused Z pass forms per frequency from the pair and the coupling of each
+ * patch's swing); results bit for bit those of the full-layout call.  3D
+ * models only (thin: WO_EUNSUPPORTED); workspace as for those calls. */
 int wo_linear_band(int32_t op, const wo_optics* o, int32_t n, const void* tf, const float* in,
                    const float* b, double eta, float* out, void* ws, size_t ws_bytes, void* stream);
+
+/* Polarisation coupling of the POL5_3D model for a swing (host only, no GPU
+ * work): kappa_cp = conj(a^H e_c) (a^H B_p e_c) for the five illumination
+ * states e_c (the extinction state e_0 = (1, i)/sqrt2 and four retarder
+ * settings of that swing), the circular analyser a = (1, -i)/sqrt2 and the
+ * property matrices B_p (phase I, rho cos 2w diag(1, -1)/2,
+ * rho sin 2w [[0, 1], [1, 0]]/2, absorption i I), computed in FP64 and
+ * rounded once to the FP32 values the kernels use:
+ * kappa_out[(c * 4 + p) * 2 + {0, 1}] = (re, im).  WO_EINVAL if swing is not
+ * finite or kappa_out is NULL. */
+int wo_pol5_coupling(double swing, float* kappa_out);
 
 /* Adjoint g_p = IFFT(sum_c conj(H_cp) R_c): r [n][C][vol] -> g_out [n][P][vol]. */
 int wo_adjoint(const wo_optics* o, int32_t n, const void* tf, const float* r, float* g_out,
                void* ws, size_t ws_bytes, void* stream);
+
 
 /* ---------------------------------------------------------------- auto-tune
  * Thin phase-from-defocus model only (WO_MODEL_LABELFREE_THIN).  Parameters
@@ -343,9 +367,12 @@ int wo_stitch_tiles(const float* tiles, int32_t ny_t, int32_t nx_t, int32_t P, i
  * while recording its tunable passes; then, pass by pass, times the whole
  * call `reps` times with every candidate schedule of that pass (the other
  * passes keeping their current schedules) and stores the one with the
- * fastest single call.
+ * fastest single call.  op | WO_FFT_TUNE_BAND runs the band-layout variant of
+ * the call instead (wo_transfer_function_band, or wo_linear_band with `tf` a
+ * band-layout bank).
  * On return `out` and `ws` hold unspecified values (run the call again);
  * tf and in are only read.  Synchronises `stream`. */
+#define WO_FFT_TUNE_BAND 16
 int wo_fft_tune(int32_t op, const wo_optics* o, int32_t n, const void* tf, const float* in, float* out,
                 double eta, int32_t reps, void* ws, size_t ws_bytes, void* stream);
 /* The table as text, one line "kind n m batch extra w threads plan" per entry

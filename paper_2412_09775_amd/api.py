@@ -40,7 +40,7 @@ SYMBOLS = ("wo_bank_shape", "wo_workspace_size", "wo_transfer_function", "wo_for
            "wo_fft_plans_export", "wo_fft_plans_import", "wo_fft_plans_clear", "wo_fft_candidates",
            "wo_tile_grid", "wo_stitch_tiles", "wo_timing_select", "wo_midband_loss_grad_aberration",
            "wo_lateral_support", "wo_transfer_function_band",
-           "wo_linear_band")
+           "wo_linear_band", "wo_pol5_coupling")
 
 _FIELDS = ("model", "nz", "ny", "nx", "dz", "dy", "dx", "wavelength", "na_ill", "na_det",
            "n_medium", "defocus", "tilt_zenith", "tilt_azimuth", "edge_width", "swing")
@@ -124,6 +124,7 @@ def load(path: str = LIB_PATH):
     lib.wo_adjoint.argtypes = [op, i32, vp, vp, vp, vp, sz, vp]
     lib.wo_transfer_function_band.argtypes = [op, i32, vp, vp, sz, vp]
     lib.wo_linear_band.argtypes = [i32, op, i32, vp, vp, vp, ctypes.c_double, vp, vp, sz, vp]
+    lib.wo_pol5_coupling.argtypes = [ctypes.c_double, ctypes.POINTER(ctypes.c_float)]
     lib.wo_strerror.argtypes = [ctypes.c_int]
     lib.wo_strerror.restype = ctypes.c_char_p
     lib.wo_version.restype = ctypes.c_int
@@ -303,11 +304,23 @@ def reconstruct(optics, tf, d, eta, b=None, ws=None, stream=None):
 
 
 def band_dims(optics):
-    """Tensor shape of one call's bank in the band layout: (n, C, P, Z, band rows, columns)."""
+    """Tensor shape of one call's bank in the band layout: (n, C, P, Z, band rows, columns);
+    the polarisation model's reduced form is the label-free pair, (n, 1, 2, ...)."""
     arr = optics_array(optics)
     C, P, dims, _ = bank_shape(optics)
+    if arr[0].model == MODEL_POL5_3D:
+        C, P = 1, 2
     sup = lateral_support(optics)
     return (len(arr), C, P, arr[0].nz, sup["band_rows"], sup["tf_cols"])
+
+
+def pol5_coupling(swing: float):
+    """The FP32 coupling kappa (5, 4) complex64 the library uses for this swing."""
+    import numpy as np
+    out = np.zeros(40, dtype=np.float32)
+    _check(load().wo_pol5_coupling(float(swing), out.ctypes.data_as(ctypes.POINTER(ctypes.c_float))),
+           "wo_pol5_coupling")
+    return out.view(np.complex64).reshape(5, 4)
 
 
 def transfer_function_band(optics, device="cuda", out=None, ws=None, stream=None):
@@ -671,16 +684,20 @@ def crop_stacks(x, out_shape, offsets=(0, 0, 0), keep_z=None, out=None, stream=N
 
 # ---------------------------------------------------------------- FFT schedule tuner
 
-def fft_tune(op, optics, tf=None, x=None, out=None, eta=0.0, reps=3, ws=None, stream=None):
+FFT_TUNE_BAND = 16   # WO_FFT_TUNE_BAND
+
+
+def fft_tune(op, optics, tf=None, x=None, out=None, eta=0.0, reps=3, ws=None, stream=None, band=False):
     """Time every candidate schedule of the FFT passes of one call (see ``wo_fft_tune``)
-    and keep the fastest; `out` and `ws` hold unspecified values afterwards."""
-    import torch
+    and keep the fastest; `out` and `ws` hold unspecified values afterwards.
+    band=True tunes the band-layout variant of the call (tf a band-layout bank)."""
     lib = load()
     arr = optics_array(optics)
     dev = out.device
     ws, _ = _workspace(optics, op, dev, ws)
-    _check(lib.wo_fft_tune(int(op), arr, len(arr), _ptr(tf), _ptr(x), _ptr(out), float(eta), int(reps),
-                           _ptr(ws), ws.numel(), _stream(stream)), "wo_fft_tune")
+    _check(lib.wo_fft_tune(int(op) | (FFT_TUNE_BAND if band else 0), arr, len(arr), _ptr(tf), _ptr(x),
+                           _ptr(out), float(eta), int(reps), _ptr(ws), ws.numel(), _stream(stream)),
+           "wo_fft_tune")
 
 
 def _text_call(fn, *args):

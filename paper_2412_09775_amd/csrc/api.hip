@@ -254,6 +254,19 @@ void pol5_kappa(double swing, double out[5][4][2]) {
   }
 }
 
+// The FP32 coupling the kernels use (each FP64 value rounded once).
+Coupling coupling_of(double swing) {
+  double k[5][4][2];
+  pol5_kappa(swing, k);
+  Coupling c;
+  for (int i = 0; i < 5; ++i)
+    for (int p = 0; p < 4; ++p)
+      for (int r = 0; r < 2; ++r) c.k[i][p][r] = (float)k[i][p][r];
+  return c;
+}
+
+bool is_pol5(const Shape& s) { return !s.thin && s.C == 5 && s.P == 4; }
+
 Sampling sampling_of(const wo_optics* o) {
   Sampling s;
   s.model = o->model;
@@ -362,7 +375,8 @@ LatSupport tf_support(const wo_optics* o, int32_t n, const Shape& s, bool* compa
   const int nv = n * field_sets(o);
   const int P3 = o->model == WO_MODEL_SECTORS9_3D ? 1 : 2;
   const long cplane = (long)sup.ly * sup.kt;
-  *compact_out = (o->model == WO_MODEL_LABELFREE_3D || o->model == WO_MODEL_SECTORS9_3D) &&
+  *compact_out = (o->model == WO_MODEL_LABELFREE_3D || o->model == WO_MODEL_SECTORS9_3D ||
+                  o->model == WO_MODEL_POL5_3D) &&
                  (sup.kt < s.Xh || sup.ky < s.Y) &&
                  compact_fields_elems(nv, nf, s, sup) + (long)nv * P3 * s.Z * cplane <=
                      (long)nv * nf * s.Z * s.Y * s.X;
@@ -378,14 +392,22 @@ size_t tf_ws(const wo_optics* o, int32_t n, const Shape& s) {
   const int nv = n * field_sets(o);
   size_t b = params_bytes(nv) + partials_bytes(o, nv);
   b += align_up((size_t)nv * nf * s.Z * s.Y * s.X * sizeof(float2));
-  if (o->model == WO_MODEL_POL5_3D) b += align_up((size_t)n * 2 * s.Z * s.Y * s.Xh * sizeof(float2));
+  // the polarisation bank's label-free pair and the coupling records
+  if (o->model == WO_MODEL_POL5_3D)
+    b += align_up((size_t)n * 2 * s.Z * s.Y * s.Xh * sizeof(float2)) + align_up((size_t)n * sizeof(Coupling));
   return b;
 }
 
-size_t linear_ws(int32_t n, const Shape& s) {
+// Spectra of the linear calls: max(C, P) channel slots per patch.
+size_t linear_spec_bytes(int32_t n, const Shape& s) {
   const int CH = s.C > s.P ? s.C : s.P;
   const long zd = s.thin ? 1 : s.Z;
   return align_up((size_t)n * CH * zd * s.Y * s.Xh * sizeof(float2));
+}
+
+// The spectra, then (polarisation model) the coupling records of the reduced bank.
+size_t linear_ws(int32_t n, const Shape& s) {
+  return linear_spec_bytes(n, s) + (is_pol5(s) ? align_up((size_t)n * sizeof(Coupling)) : 0);
 }
 
 #define WO_TRY(expr)                         \
@@ -442,7 +464,8 @@ int linear_in(const wo_optics* o, int32_t n, const Shape& s, const float* in, in
 // wo_transfer_function_band) instead of [C][P][Z][Y][Xh]; the two coincide
 // where the support fills the grid.
 int linear_out(const wo_optics* o, int32_t n, const Shape& s, const float2* tf, float* out,
-               const float* bg, int mode, float eta, void* ws, hipStream_t st, bool bank_band = false) {
+               const float* bg, int mode, float eta, void* ws, hipStream_t st, bool bank_band = false,
+               const Coupling* cpl = nullptr) {
   const LinearPlan p = linear_plan(o, n, s, mode);
   float2* spec = (float2*)ws;
   const long M = s.Y * s.Xh;
@@ -451,7 +474,7 @@ int linear_out(const wo_optics* o, int32_t n, const Shape& s, const float2* tf, 
   RowGroups gout{p.cout * p.zd * s.Y, p.CH * p.zd * s.Y, p.cout * p.zd * s.Y, n};
   if (p.banded) {
     const SpecBand band{(int)s.Y, p.kt, p.ky, bank_band ? 1 : 0};
-    WO_TRY(launch_zop(spec, tf, s.C, s.P, (int)s.Z, M, p.CH, n, mode, eta, bg, inv_n, nfull, st, &band));
+    WO_TRY(launch_zop(spec, tf, s.C, s.P, (int)s.Z, M, p.CH, n, mode, eta, bg, inv_n, nfull, st, &band, cpl));
     WO_TRY(launch_cols(spec, (int)s.Y, p.kt, p.cout * p.zd, p.CH * p.zd, n, 1.f, st, "k_cols_y_inv", 2,
                        p.ky));
     WO_TRY(launch_rows_c2r(spec, out, (int)s.X, gout, 1.f, st, p.kt, p.kt));
@@ -460,19 +483,29 @@ int linear_out(const wo_optics* o, int32_t n, const Shape& s, const float2* tf, 
   if (s.thin) {
     WO_TRY(launch_op2d(spec, tf, s.C, s.P, M, p.CH, n, mode, eta, bg, inv_n, nfull, st));
   } else {
-    WO_TRY(launch_zop(spec, tf, s.C, s.P, (int)s.Z, M, p.CH, n, mode, eta, bg, inv_n, nfull, st));
+    WO_TRY(launch_zop(spec, tf, s.C, s.P, (int)s.Z, M, p.CH, n, mode, eta, bg, inv_n, nfull, st, nullptr,
+                      cpl));
   }
   WO_TRY(launch_cols(spec, (int)s.Y, s.Xh, p.cout * p.zd, p.CH * p.zd, n, 1.f, st, "k_cols_y_inv"));
   WO_TRY(launch_rows_c2r(spec, out, (int)s.X, gout, 1.f, st));
   return WO_OK;
 }
 
+// reduced: tf is the polarisation bank in reduced form (the label-free pair);
+// the coupling records go into the workspace behind the spectra.
 int run_linear(const wo_optics* o, int32_t n, const Shape& s, const float2* tf, const float* in,
                float* out, const float* bg, int mode, float eta, void* ws, hipStream_t st,
-               bool bank_band = false) {
+               bool bank_band = false, bool reduced = false) {
+  Coupling* cpl = nullptr;
+  if (reduced) {
+    cpl = (Coupling*)((char*)ws + linear_spec_bytes(n, s));
+    std::vector<Coupling> h(n);
+    for (int i = 0; i < n; ++i) h[i] = coupling_of(o[i].swing);
+    WO_TRY(launch_set_coupling(cpl, h.data(), n, st));
+  }
   int r = linear_in(o, n, s, in, mode, ws, st);
   if (r) return r;
-  return linear_out(o, n, s, tf, out, bg, mode, eta, ws, st, bank_band);
+  return linear_out(o, n, s, tf, out, bg, mode, eta, ws, st, bank_band, cpl);
 }
 
 // ---------------------------------------------------------------- auto-tune
@@ -1152,7 +1185,6 @@ static int run_tf(const wo_optics* o, int32_t n, const Shape& s, void* tf_out, v
       DevOptics& d = h[i * fs + c];
       d = dev_optics(o[i]);
       if (fs == 9) d.sector = c < 8 ? c : -1;
-      if (o[i].model == WO_MODEL_POL5_3D) pol5_kappa(o[i].swing, d.kappa);
     }
   char* w = (char*)ws;
   DevOptics* dopt = (DevOptics*)w;
@@ -1220,11 +1252,33 @@ static int run_tf(const wo_optics* o, int32_t n, const Shape& s, void* tf_out, v
       }
       break;
     case WO_MODEL_POL5_3D: {
-      float2* uw = (float2*)w;
-      WO_TRY(launch_tf_rows_labelfree(partials, sm, n, ab, uw, 2 * s.Z * plane, s.Z * plane, plane, hs,
-                                      &full_out));
-      WO_TRY(launch_cols(uw, (int)s.Y, s.Xh, 2 * s.Z, 2 * s.Z, n, -1.f, hs, "k_cols_y_tf"));
-      WO_TRY(launch_tf_pol5_z(dopt, sm, n, uw, tf, hs));
+      // The 5 x 4 bank is the label-free pair mixed by a constant coupling:
+      // the pair in the band layout [2][Z][band rows][kt] (the full layout
+      // where the support fills the grid) is the reduced bank, written to
+      // tf_out (band_out) or to the workspace and expanded into the full bank.
+      float2* red = band_out ? tf : (float2*)w;
+      int kt = (int)s.Xh, ky = (int)s.Y;
+      if (compact_out) {
+        WO_TRY(launch_tf_rows_labelfree(partials, sm, n, ab, cb, 2 * s.Z * cplane, s.Z * cplane, cplane,
+                                        hs, &sup, sup.kt));
+        WO_TRY(launch_cols(cb, sup.ly, sup.kt, 2 * s.Z, 2 * s.Z, n, -1.f, hs, "k_cols_y_tf", 1, sup.ky));
+        WO_TRY(launch_cols_expand(cb, red, (int)s.Z, sup.ly, (int)s.Y, (int)s.Xh, sup.kt, sup.ky, 2L * n,
+                                  -1.f, hs, true));
+        kt = sup.kt;
+        ky = sup.ky;
+      } else {
+        WO_TRY(launch_tf_rows_labelfree(partials, sm, n, ab, red, 2 * s.Z * plane, s.Z * plane, plane, hs,
+                                        &full_out));
+        WO_TRY(launch_cols(red, (int)s.Y, s.Xh, 2 * s.Z, 2 * s.Z, n, -1.f, hs, "k_cols_y_tf"));
+        WO_TRY(launch_cols(red, (int)s.Z, M, 2, 2, n, -1.f, hs, "k_cols_z_tf"));
+      }
+      if (!band_out) {
+        Coupling* cp = (Coupling*)((char*)w + align_up((size_t)n * 2 * s.Z * s.Y * s.Xh * sizeof(float2)));
+        std::vector<Coupling> hc(n);
+        for (int i = 0; i < n; ++i) hc[i] = coupling_of(o[i].swing);
+        WO_TRY(launch_set_coupling(cp, hc.data(), n, hs));
+        WO_TRY(launch_pol5_mix(cp, red, tf, (int)s.Z, (int)s.Y, (int)s.Xh, kt, ky, n, hs));
+      }
       break;
     }
     default:
@@ -1260,6 +1314,13 @@ int wo_transfer_function_band(const wo_optics* o, int32_t n, void* tf_out, void*
   return run_tf(o, n, s, tf_out, ws, (hipStream_t)stream, true);
 }
 
+int wo_pol5_coupling(double swing, float* kappa_out) {
+  if (!kappa_out || !isfinite(swing)) return WO_EINVAL;
+  const Coupling c = coupling_of(swing);
+  memcpy(kappa_out, &c.k[0][0][0], sizeof(c.k));
+  return WO_OK;
+}
+
 int wo_linear_band(int32_t op, const wo_optics* o, int32_t n, const void* tf, const float* in,
                    const float* b, double eta, float* out, void* ws, size_t ws_bytes, void* stream) {
   if (!o || n < 1) return WO_EINVAL;
@@ -1281,7 +1342,7 @@ int wo_linear_band(int32_t op, const wo_optics* o, int32_t n, const void* tf, co
   }
   if (ws_bytes < linear_ws(n, s)) return WO_ENOMEM;
   return run_linear(o, n, s, (const float2*)tf, in, out, mode == kModeAdjoint ? nullptr : b, mode,
-                    mode == kModeSolve ? (float)eta : 0.f, ws, (hipStream_t)stream, true);
+                    mode == kModeSolve ? (float)eta : 0.f, ws, (hipStream_t)stream, true, is_pol5(s));
 }
 
 int wo_forward(const wo_optics* o, int32_t n, const void* tf, const float* f, const float* b,
@@ -1338,6 +1399,8 @@ int wo_adjoint(const wo_optics* o, int32_t n, const void* tf, const float* r, fl
 }
 
 }  // extern "C"
+
+
 
 extern "C" {
 

@@ -447,11 +447,26 @@ struct DevOptics {
   double wavelength, na_ill, na_det, n_medium;
   double defocus, tilt_zenith, tilt_azimuth;
   double edge_width;       // half-width of the soft edge, in frequency pixels
-  double kappa[5][4][2];   // polarisation coupling (re, im), pol5 only
   double ibg;
   int sector;              // illumination aperture: -1 the full disc, 0..7 an azimuthal sector
   float zern[7];           // detection aberration, waves, Noll j = 5..11
 };
+
+// Polarisation coupling kappa_cp of one patch in FP32, (re, im) per channel c
+// and property p: the values every kernel that forms the 5 x 4 bank uses.
+struct Coupling {
+  float k[5][4][2];
+};
+
+// One entry of the polarisation bank from the label-free pair at a frequency:
+// H_cp = Re(kappa_cp) H_phase + Im(kappa_cp) H_abs (the paraxial Jones
+// reduction of Table 1's vector row).  Each product and the sum are rounded
+// on their own (no fused multiply-add), so the bank expansion, the fused Z
+// pass and a plain FP32 evaluation on the host give the same bits.
+__device__ __forceinline__ float2 pol5_entry(float kr, float ki, float2 hp, float2 ha) {
+#pragma clang fp contract(off)
+  return make_float2(kr * hp.x + ki * ha.x, kr * hp.y + ki * ha.y);
+}
 
 // Detection aberration W(p) in waves: sum of zern[j - 5] Z_j over Noll's
 // unit-RMS Zernike polynomials j = 5..11 at rho = |p| / (NA_det / lambda0),

@@ -577,6 +577,51 @@ hipError_t launch_cols_expand(const float2* src, float2* dst, int N, int Ys, int
   return hipGetLastError();
 }
 
+// ------------------------------------------------------------------ polarisation bank expansion
+
+// One thread per (z, y, k) of a patch's half-spectrum plane stack: reads the
+// label-free pair there (zero off the band rows and columns k >= kt) and writes
+// the 20 entries of the 5 x 4 bank, contiguous in k for each entry.
+__global__ __launch_bounds__(256) void k_pol5_mix(const Coupling* __restrict__ cpl,
+                                                  const float2* __restrict__ red,
+                                                  float2* __restrict__ tf, int Z, int Y, int Xh,
+                                                  int kt, int ky, int nb, long per_patch) {
+  const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long patch = blockIdx.y;
+  if (gid >= per_patch) return;
+  const int k = (int)(gid % Xh);
+  const long zy = gid / Xh;
+  const int y = (int)(zy % Y), z = (int)(zy / Y);
+  const bool on = k < kt && in_band(y, ky, nb, Y);
+  float2 u = make_float2(0.f, 0.f), v = u;
+  if (on) {
+    const int b = (nb == Y || y <= ky) ? y : y - (Y - nb);
+    const long rp = (long)Z * nb * kt;          // one reduced volume
+    const float2* src = red + patch * 2 * rp + ((long)z * nb + b) * kt + k;
+    u = src[0];
+    v = src[rp];
+  }
+  const float* kf = &cpl[patch].k[0][0][0];
+  float2* dst = tf + patch * 20 * per_patch + gid;
+#pragma unroll
+  for (int j = 0; j < 20; ++j)
+    dst[j * per_patch] = on ? pol5_entry(kf[2 * j], kf[2 * j + 1], u, v) : make_float2(0.f, 0.f);
+}
+
+hipError_t launch_pol5_mix(const Coupling* cpl, const float2* red, float2* tf, int Z, int Y, int Xh,
+                           int kt, int ky, int npatch, hipStream_t s) {
+  if (kt < 1 || kt > Xh || ky < 0 || npatch < 1 || npatch > 65535) return hipErrorInvalidValue;
+  const int nb = 2L * ky + 1 < Y ? 2 * ky + 1 : Y;
+  const int kyn = nb == Y ? Y : ky;
+  const long per_patch = (long)Z * Y * Xh;
+  const long blocks = (per_patch + 255) / 256;
+  if (blocks > 0x7fffffffL) return hipErrorInvalidValue;
+  ScopedTiming _t("k_pol5_mix", s);
+  hipLaunchKernelGGL(k_pol5_mix, dim3((unsigned)blocks, (unsigned)npatch), dim3(256), 0, s, cpl, red, tf,
+                     Z, Y, Xh, kt, kyn, nb, per_patch);
+  return hipGetLastError();
+}
+
 // ------------------------------------------------------------------ per-frequency operators
 //
 // Channel values of one frequency sit at cell[ch * cs].  H(c, p) returns the
@@ -617,6 +662,23 @@ __device__ __forceinline__ void freq_op(float2* cell, long cs, HF H, int Crt, in
     }
 #pragma unroll
     for (int p = 0; p < P; ++p) cell[p * cs] = cscale(y[p], inv_n);
+    return;
+  }
+  if constexpr (CT == 1) {
+    // one channel: H is a row h, and (h^H h + eta I)^-1 h^H = h^H / (h h^H + eta)
+    // (Sherman-Morrison), so F_p = conj(h_p) x / (sum_q |h_q|^2 + eta)
+    float2 xc = cell[0];
+    if (dc && bg) xc.x -= n_full * bg[0];
+    float2 h[P];
+    float den = eta;
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+      h[p] = H(0, p);
+      den += h[p].x * h[p].x + h[p].y * h[p].y;
+    }
+    const float sc = den > 0.f ? inv_n / den : 0.f;
+#pragma unroll
+    for (int p = 0; p < P; ++p) cell[p * cs] = cscale(cmulconj(xc, h[p]), sc);
     return;
   }
   // solve: accumulate the lower triangle of M = H^H H, M_pq = sum_c conj(H_cp) H_cq,
@@ -700,12 +762,15 @@ struct ZopGeom {
 
 // With compiled stages at most 72 VGPRs (7 waves per SIMD, no spills); the
 // runtime-plan instances keep their allocation (they would spill).
-template <int P, int CT, int NS>
+// RED: tf holds the polarisation bank in reduced form, [2][Z][..] per patch
+// (H_phase, H_abs), and the coupling cpl[patch] forms H_cp per frequency.
+template <int P, int CT, int NS, bool RED>
 __global__ __launch_bounds__(1024, NS > 0 ? 7 : 1) void k_zop(float2* __restrict__ spec,
                                               const float2* __restrict__ tf, int C, int Z, ZopGeom gm,
                                               int slots, int W, long tiles_m, FftPlan plan,
                                               int mode, float eta, const float* __restrict__ bg,
-                                              float inv_n, float n_full) {
+                                              float inv_n, float n_full,
+                                              const Coupling* __restrict__ cpl) {
   extern __shared__ float2 smem[];
   float2* tw = smem;
   float2* buf = smem + Z;
@@ -720,7 +785,7 @@ __global__ __launch_bounds__(1024, NS > 0 ? 7 : 1) void k_zop(float2* __restrict
   const int CH = cin > cout ? cin : cout;
   const long Ms = gm.Ms, Mt = gm.Mt;
   float2* sp = spec + patch * (long)slots * Z * Ms;
-  const float2* tp = tf + patch * (long)C * P * Z * Mt;
+  const float2* tp = tf + patch * (long)(RED ? 2 : C * P) * Z * Mt;
   const float* bp = bg ? bg + patch * C : nullptr;
   const int brow = (int)(tile / gm.tiles_row);
   const long col0 = (tile - (long)brow * gm.tiles_row) * W;
@@ -734,7 +799,7 @@ __global__ __launch_bounds__(1024, NS > 0 ? 7 : 1) void k_zop(float2* __restrict
   // data tile is loaded and transformed.  Frequency f = tid + i * nthr.
   const int nfreq = Zc * W;
   const int fpt = (nfreq + nthr - 1) / nthr;
-  const bool prefetch = CT == 1 && P * fpt <= kTfPrefetch;
+  const bool prefetch = !RED && CT == 1 && P * fpt <= kTfPrefetch;
   float2 hreg[kTfPrefetch];
   if (prefetch) {
 #pragma unroll
@@ -803,9 +868,19 @@ __global__ __launch_bounds__(1024, NS > 0 ? 7 : 1) void k_zop(float2* __restrict
       const int z = f >> wsh, w = f & (W - 1);
       if (w >= weff) continue;
       const float2* hp = tp + (long)z * Mt + mt0 + w;
-      freq_op<P, CT>(buf + (long)z * CH * W + w, W,
-                     [&](int c, int p) { return hp[(long)(c * P + p) * ts]; }, C, mode, eta, bp,
-                     z == 0 && dc_tile && w == 0, n_full, inv_n);
+      if constexpr (RED) {
+        const float2 hph = hp[0], hab = hp[ts];
+        const float* kf = &cpl[patch].k[0][0][0];
+        freq_op<P, CT>(buf + (long)z * CH * W + w, W,
+                       [&](int c, int p) {
+                         return pol5_entry(kf[(c * P + p) * 2], kf[(c * P + p) * 2 + 1], hph, hab);
+                       },
+                       C, mode, eta, bp, z == 0 && dc_tile && w == 0, n_full, inv_n);
+      } else {
+        freq_op<P, CT>(buf + (long)z * CH * W + w, W,
+                       [&](int c, int p) { return hp[(long)(c * P + p) * ts]; }, C, mode, eta, bp,
+                       z == 0 && dc_tile && w == 0, n_full, inv_n);
+      }
     }
   }
   __syncthreads();
@@ -844,14 +919,15 @@ __global__ __launch_bounds__(1024, NS > 0 ? 7 : 1) void k_zop(float2* __restrict
   }
 }
 
-template <int P, int CT>
+template <int P, int CT, bool RED = false>
 static void zop_launch(bool use_static, long nwg, int thr, size_t lds, hipStream_t s, float2* spec,
                        const float2* tf, int C, int Z, const ZopGeom& gm, int slots, int W, long tiles,
-                       FftPlan plan, int mode, float eta, const float* bg, float inv_n, float nf) {
+                       FftPlan plan, int mode, float eta, const float* bg, float inv_n, float nf,
+                       const Coupling* cpl) {
 #define X_(NN)                                                                                   \
   case NN:                                                                                       \
-    hipLaunchKernelGGL((k_zop<P, CT, NN>), dim3((unsigned)nwg), dim3(thr), lds, s, spec, tf, C, Z, gm, \
-                       slots, W, tiles, plan, mode, eta, bg, inv_n, nf);                         \
+    hipLaunchKernelGGL((k_zop<P, CT, NN, RED>), dim3((unsigned)nwg), dim3(thr), lds, s, spec, tf, C, Z, \
+                       gm, slots, W, tiles, plan, mode, eta, bg, inv_n, nf, cpl);                \
     return;
   if (use_static) switch (Z) {
       WO_AXIAL_SIZES(X_)
@@ -859,8 +935,8 @@ static void zop_launch(bool use_static, long nwg, int thr, size_t lds, hipStream
         break;
     }
 #undef X_
-  hipLaunchKernelGGL((k_zop<P, CT, 0>), dim3((unsigned)nwg), dim3(thr), lds, s, spec, tf, C, Z, gm,
-                     slots, W, tiles, plan, mode, eta, bg, inv_n, nf);
+  hipLaunchKernelGGL((k_zop<P, CT, 0, RED>), dim3((unsigned)nwg), dim3(thr), lds, s, spec, tf, C, Z, gm,
+                     slots, W, tiles, plan, mode, eta, bg, inv_n, nf, cpl);
 }
 
 static bool zop_choice_ok(int Z, int CH, const FftChoice& c) {
@@ -878,7 +954,8 @@ bool zop_fits(int Z, int CH) { return zop_choice_ok(Z, CH, zop_default(Z, CH)); 
 
 hipError_t launch_zop(float2* spec, const float2* tf, int C, int P, int Z, long M, int slots,
                       int npatch, int mode, float eta, const float* bg, float inv_n, double n_full,
-                      hipStream_t s, const SpecBand* band) {
+                      hipStream_t s, const SpecBand* band, const Coupling* cpl) {
+  if (cpl && (P != 4 || C != 5)) return hipErrorInvalidValue;
   if (band && (band->Y < 1 || M % band->Y != 0 || band->kt < 1 || band->kt > M / band->Y ||
                band->ky < 0))
     return hipErrorInvalidValue;
@@ -886,11 +963,12 @@ hipError_t launch_zop(float2* spec, const float2* tf, int C, int P, int Z, long 
   const SpecBand bc = hb ? *band : SpecBand{1, M, 0, 0};
   const int nbr = hb ? (2L * bc.ky + 1 >= bc.Y ? bc.Y : 2 * bc.ky + 1) : 1;
   const long mcov = hb ? (long)nbr * bc.kt : M;   // columns the pass covers per plane
-  const FftKey key{kFftZop, Z, mcov, npatch, P * 1000 + C * 10 + mode + (hb ? 100000 : 0)};
+  const FftKey key{kFftZop, Z, mcov, npatch,
+                   P * 1000 + C * 10 + mode + (hb ? 100000 : 0) + (cpl ? 200000 : 0)};
   if (fft_recording())
     fft_record(key, [=] {
       return launch_zop(spec, tf, C, P, Z, M, slots, npatch, mode, eta, bg, inv_n, n_full, s,
-                        hb ? &bc : nullptr);
+                        hb ? &bc : nullptr, cpl);
     });
   const int cin = mode == kModeForward ? P : C;
   const int cout = mode == kModeForward ? C : P;
@@ -919,10 +997,13 @@ hipError_t launch_zop(float2* spec, const float2* tf, int C, int P, int Z, long 
   const bool st = c.plan == 0;
   ScopedTiming _t(P == 1 ? "k_zop<1>" : (P == 2 ? "k_zop<2>" : "k_zop<4>"), s);
 #define WO_ZOP(PP, CC) \
-  zop_launch<PP, CC>(st, nwg, thr, lds, s, spec, tf, C, Z, gm, slots, W, tiles, plan, mode, eta, bg, inv_n, nf)
-  if (P == 1) { if (C == 1) WO_ZOP(1, 1); else WO_ZOP(1, 0); }
+  zop_launch<PP, CC>(st, nwg, thr, lds, s, spec, tf, C, Z, gm, slots, W, tiles, plan, mode, eta, bg, inv_n, nf, \
+                     nullptr)
+  if (cpl) zop_launch<4, 5, true>(st, nwg, thr, lds, s, spec, tf, C, Z, gm, slots, W, tiles, plan, mode, eta,
+                                  bg, inv_n, nf, cpl);
+  else if (P == 1) { if (C == 1) WO_ZOP(1, 1); else WO_ZOP(1, 0); }
   else if (P == 2) { if (C == 1) WO_ZOP(2, 1); else WO_ZOP(2, 0); }
-  else if (P == 4) { if (C == 1) WO_ZOP(4, 1); else WO_ZOP(4, 0); }
+  else if (P == 4) { if (C == 1) WO_ZOP(4, 1); else if (C == 5) WO_ZOP(4, 5); else WO_ZOP(4, 0); }
   else return hipErrorInvalidValue;
 #undef WO_ZOP
   return hipGetLastError();

@@ -148,9 +148,18 @@ struct SpecBand {
 // With a band, spec holds `slots` slots of [Z][Y][kt] instead (M = Y * Xh
 // stays the bank's plane) and only the band rows' columns k < kt are
 // transformed; the rest of spec is left as it is.
+// cpl (not NULL; P = 4, C = 5): tf holds the polarisation bank in reduced
+// form, [2][Z][..] per patch (H_phase, H_abs) in the layout the band gives, and
+// H_cp = pol5_entry(cpl[patch].k[c][p], H_phase, H_abs) is formed per frequency.
 hipError_t launch_zop(float2* spec, const float2* tf, int C, int P, int Z, long M, int slots,
                       int npatch, int mode, float eta, const float* bg, float inv_n, double n_full,
-                      hipStream_t s, const SpecBand* band = nullptr);
+                      hipStream_t s, const SpecBand* band = nullptr, const Coupling* cpl = nullptr);
+// The 5 x 4 polarisation bank tf [patch][5][4][Z][Y][Xh] from its reduced form
+// red [patch][2][Z][nb][kt] (H_phase, H_abs on the band rows of kt columns; nb =
+// Y and kt = Xh: the full layout): H_cp = pol5_entry(kappa_cp, ...) on the
+// support, exact zeros elsewhere.
+hipError_t launch_pol5_mix(const Coupling* cpl, const float2* red, float2* tf, int Z, int Y, int Xh,
+                           int kt, int ky, int npatch, hipStream_t s);
 // 2D (thin) per-frequency op: spec [slots][M] per patch, tf [C][P][M] per patch.
 // eta_pp (device [npatch], may be NULL) overrides eta per patch.
 hipError_t launch_op2d(float2* spec, const float2* tf, int C, int P, long M, int slots, int npatch,
@@ -197,8 +206,7 @@ hipError_t launch_tf_rows_labelfree(const double* partials, const Sampling& sm, 
                                     const LatSupport* sup = nullptr, int pitch = 0);
 hipError_t launch_tf_rows_fluor(const double* partials, const Sampling& sm, int npatch,
                                 const float2* h, float2* out, hipStream_t s);
-hipError_t launch_tf_pol5_z(const DevOptics* opt, const Sampling& sm, int npatch, float2* uw,
-                            float2* tf, hipStream_t s);
+hipError_t launch_set_coupling(Coupling* dst, const Coupling* host, int n, hipStream_t s);
 
 // Auto-tune (thin model).
 hipError_t launch_set_tune(TuneState* dst, const TuneState* host, int n, hipStream_t s);

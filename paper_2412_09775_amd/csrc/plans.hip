@@ -118,8 +118,14 @@ int wo_fft_tune(int32_t op, const wo_optics* o, int32_t n, const void* tf, const
                 double eta, int32_t reps, void* ws, size_t ws_bytes, void* stream) {
   if (!o || n < 1 || reps < 1 || !ws) return WO_EINVAL;
   hipStream_t hs = (hipStream_t)stream;
+  const bool band = (op & WO_FFT_TUNE_BAND) != 0;
+  const int op0 = op & ~WO_FFT_TUNE_BAND;
   auto run_op = [&]() -> int {
-    switch (op) {
+    if (band)
+      return op0 == WO_OP_TRANSFER_FUNCTION
+                 ? wo_transfer_function_band(o, n, out, ws, ws_bytes, stream)
+                 : wo_linear_band(op0, o, n, tf, in, nullptr, eta, out, ws, ws_bytes, stream);
+    switch (op0) {
       case WO_OP_TRANSFER_FUNCTION: return wo_transfer_function(o, n, out, ws, ws_bytes, stream);
       case WO_OP_FORWARD: return wo_forward(o, n, tf, in, nullptr, out, ws, ws_bytes, stream);
       case WO_OP_RECONSTRUCT: return wo_reconstruct(o, n, tf, in, nullptr, eta, out, ws, ws_bytes, stream);

@@ -40,6 +40,28 @@ hipError_t launch_set_params(DevOptics* dst, const DevOptics* host, int n, hipSt
   return hipSuccess;
 }
 
+struct CouplingBatch {
+  Coupling c[16];
+};
+static_assert(sizeof(CouplingBatch) <= 3584, "kernel arguments are limited to 4 KiB");
+
+__global__ void k_set_coupling(Coupling* dst, CouplingBatch b, int count) {
+  const int i = threadIdx.x;
+  if (i < count) dst[i] = b.c[i];
+}
+
+hipError_t launch_set_coupling(Coupling* dst, const Coupling* host, int n, hipStream_t s) {
+  for (int i0 = 0; i0 < n; i0 += 16) {
+    CouplingBatch b;
+    const int cnt = n - i0 < 16 ? n - i0 : 16;
+    for (int j = 0; j < cnt; ++j) b.c[j] = host[i0 + j];
+    hipLaunchKernelGGL(k_set_coupling, dim3(1), dim3(64), 0, s, dst + i0, b, cnt);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 struct TuneBatch {
   TuneState t[8];
 };
@@ -719,97 +741,6 @@ hipError_t launch_tf_rows_fluor(const double* partials, const Sampling& sm, int 
 #undef X_
   hipLaunchKernelGGL((k_tf_rows_fl<0>), dim3((unsigned)nwg), dim3(thr), lds, s, partials, tiles_x, sm, h,
                      out, Q, wpp, plan);
-  return hipGetLastError();
-}
-
-// ------------------------------------------------------------------ polarisation bank, Z pass
-
-// uw: [patch][2][Z][M] (phase, absorption half spectra after the Y pass);
-// tf: [patch][5][4][Z][M], H_cp = Re(kappa_cp) U + Im(kappa_cp) V after the Z transform.
-template <int NS>
-__global__ __launch_bounds__(1024) void k_tf_pol5_z(const DevOptics* __restrict__ opt, int Z,
-                                                    long M, const float2* __restrict__ uw,
-                                                    float2* __restrict__ tf, int W, long tiles_m,
-                                                    FftPlan plan) {
-  extern __shared__ float2 smem[];
-  float2* tw = smem;
-  float2* buf = smem + Z;
-  const int tid = threadIdx.x, nthr = blockDim.x;
-  fill_twiddles(tw, Z, tid, nthr);
-  const long tile = blockIdx.x % tiles_m;
-  const long patch = blockIdx.x / tiles_m;
-  const long m0 = tile * W;
-  const int weff = (int)min((long)W, M - m0);
-  const float2* src = uw + patch * 2L * Z * M;
-  {
-    float2 t[kEmax];
-#pragma unroll
-    for (int i = 0; i < kEmax; ++i) {
-      const int e = tid + i * nthr;
-      if (e < 2 * Z * W) {
-        const int w = e % W, r = e / W;
-        const int z = r % Z, f = r / Z;
-        t[i] = w < weff ? src[((long)f * Z + z) * M + m0 + w] : make_float2(0.f, 0.f);
-      }
-    }
-#pragma unroll
-    for (int i = 0; i < kEmax; ++i) {
-      const int e = tid + i * nthr;
-      if (e < 2 * Z * W) {
-        const int w = e % W, r = e / W;
-        const int z = r % Z, f = r / Z;
-        buf[(z * 2 + f) * W + w] = t[i];
-      }
-    }
-  }
-  __syncthreads();
-  fft_lines<NS, 0, true>(buf, LdsLines{2 * W, 2 * W, 1, true, pow2_shift(2 * W)}, plan, tw, -1.f, tid,
-                         nthr);
-  float kr[20], ki[20];
-  const DevOptics& o = opt[patch];
-#pragma unroll
-  for (int j = 0; j < 20; ++j) {
-    kr[j] = (float)o.kappa[j / 4][j % 4][0];
-    ki[j] = (float)o.kappa[j / 4][j % 4][1];
-  }
-  float2* dst = tf + patch * 20L * Z * M;
-  for (int e = tid; e < Z * W; e += nthr) {
-    const int z = e / W, w = e - z * W;
-    if (w >= weff) continue;
-    const float2 u = buf[(z * 2) * W + w], v = buf[(z * 2 + 1) * W + w];
-#pragma unroll
-    for (int j = 0; j < 20; ++j)
-      dst[((long)j * Z + z) * M + m0 + w] =
-          make_float2(kr[j] * u.x + ki[j] * v.x, kr[j] * u.y + ki[j] * v.y);
-  }
-}
-
-hipError_t launch_tf_pol5_z(const DevOptics* opt, const Sampling& sm, int npatch, float2* uw,
-                            float2* tf, hipStream_t s) {
-  FftPlan plan;
-  if (!make_plan(sm.nz, &plan)) return hipErrorInvalidValue;
-  const long M = (long)sm.ny * (sm.nx / 2 + 1);
-  const long lim = lds_limit_bytes() / (long)sizeof(float2);
-  int W = 16;
-  while (W > 1 && (2L * W * sm.nz > kMaxElems || sm.nz + 2L * W * sm.nz > lim)) W /= 2;
-  const long tiles = (M + W - 1) / W;
-  const long nwg = tiles * npatch;
-  const int thr = threads_for(2L * sm.nz * W);
-  const size_t lds = (size_t)(sm.nz + 2 * sm.nz * W) * sizeof(float2);
-  ScopedTiming _t("k_tf_pol5_z", s);
-#define X_(NN)                                                                                   \
-  case NN:                                                                                       \
-    hipLaunchKernelGGL((k_tf_pol5_z<NN>), dim3((unsigned)nwg), dim3(thr), lds, s, opt, sm.nz, M, uw, \
-                       tf, W, tiles, plan);                                                      \
-    return hipGetLastError();
-  switch (sm.nz) {
-    WO_AXIAL_SIZES(X_)
-    default:
-      break;
-  }
-#undef X_
-  hipLaunchKernelGGL((k_tf_pol5_z<0>), dim3((unsigned)nwg), dim3(thr), lds, s, opt, sm.nz, M, uw, tf, W,
-                     tiles, plan);
   return hipGetLastError();
 }
 

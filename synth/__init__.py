@@ -8,6 +8,6 @@ both sides receive).
 """
 
 from .objects import (  # noqa: F401
-    beads, ellipsoids, fibres, thin_cells, poisson_gaussian, gaussian_noise,
+    beads, ellipsoids, fibres, fibres_on_device, thin_cells, poisson_gaussian, gaussian_noise,
     plane_waves,
 )

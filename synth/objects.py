@@ -83,12 +83,15 @@ def _catmull_rom(ctrl: np.ndarray, n: int) -> np.ndarray:
 
 
 def fibres(shape, voxel, n, seed, sigma=0.15, retardance_nm=(0.0, 5.0), dn=(0.01, 0.05),
-           wavelength=0.532, batch=16) -> np.ndarray:
+           wavelength=0.532, batch=64) -> np.ndarray:
     """Spline fibres with a Gaussian cross-section; returns (4, Z, Y, X).
 
     Properties per voxel: [phase, rho cos 2w, rho sin 2w, absorption(=0)], where
     rho = 2 pi retardance / lambda0 and w ~ U(0, pi) is the fibre's orientation;
     the profile is 1 on the fibre axis and falls off as exp(-r^2 / 2 sigma^2).
+    Each fibre is a chain of points sigma/2 apart, each point spreading a 3D
+    Gaussian (the product of one Gaussian per axis) over the voxels within
+    3 sigma of it.
     """
     rng = np.random.default_rng(seed)
     Z, Y, X = shape
@@ -98,7 +101,6 @@ def fibres(shape, voxel, n, seed, sigma=0.15, retardance_nm=(0.0, 5.0), dn=(0.01
     out = np.zeros((3, nvox), dtype=np.float64)
     step = sigma / 2.0
     half = np.ceil(3 * sigma / vox).astype(int)
-    offs = np.stack(np.meshgrid(*(np.arange(-h, h + 1) for h in half), indexing="ij"), -1).reshape(-1, 3)
     pend_idx, pend_w = [], []
 
     def flush():
@@ -107,7 +109,7 @@ def fibres(shape, voxel, n, seed, sigma=0.15, retardance_nm=(0.0, 5.0), dn=(0.01
         idx = np.concatenate(pend_idx)
         w = np.concatenate(pend_w, axis=1)
         for j in range(3):
-            out[j] += np.bincount(idx, weights=w[j], minlength=nvox)
+            np.add.at(out[j], idx, w[j])
         pend_idx.clear()
         pend_w.clear()
 
@@ -124,20 +126,73 @@ def fibres(shape, voxel, n, seed, sigma=0.15, retardance_nm=(0.0, 5.0), dn=(0.01
         si = np.linspace(0.0, s[-1], npts)
         pts = np.stack([np.interp(si, s, dense[:, k]) for k in range(3)], -1)
         ds = s[-1] / (npts - 1)
-        base = np.rint(pts / vox).astype(int)
-        cells = base[:, None, :] + offs[None, :, :]
-        d2 = np.sum(((cells * vox) - pts[:, None, :]) ** 2, axis=-1)
-        wgt = np.exp(-d2 / (2 * sigma * sigma)) * ds / (math.sqrt(2 * math.pi) * sigma)
-        ok = np.all((cells >= 0) & (cells < np.array(shape)), axis=-1)
-        flat = (cells[..., 0] * Y + cells[..., 1]) * X + cells[..., 2]
-        pend_idx.append(flat[ok])
-        pend_w.append(vals[:, None] * wgt[ok][None, :])
+        base = np.rint(pts / vox).astype(np.int64)
+        # per axis: the cells within 3 sigma, their 1D Gaussian factor and validity
+        cell, g, ok = [], [], []
+        for a in range(3):
+            c = base[:, a, None] + np.arange(-half[a], half[a] + 1)[None, :]
+            g.append(np.exp(-((c * vox[a] - pts[:, a, None]) ** 2) / (2 * sigma * sigma)))
+            cell.append(c)
+            ok.append((c >= 0) & (c < shape[a]))
+        wgt = (g[0][:, :, None, None] * g[1][:, None, :, None] * g[2][:, None, None, :]
+               * (ds / (math.sqrt(2 * math.pi) * sigma)))
+        flat = ((cell[0][:, :, None, None] * Y + cell[1][:, None, :, None]) * X + cell[2][:, None, None, :])
+        keep = ok[0][:, :, None, None] & ok[1][:, None, :, None] & ok[2][:, None, None, :]
+        wk = wgt[keep]
+        pend_idx.append(flat[keep])
+        pend_w.append(vals[:, None] * wk[None, :])
         if (i + 1) % batch == 0:
             flush()
     flush()
     res = np.zeros((4, nvox), dtype=np.float32)
     res[:3] = out
     return res.reshape((4,) + tuple(shape))
+
+
+def fibres_on_device(shape, voxel, n, seed, device, sigma=0.15, retardance_nm=(0.0, 5.0),
+                     dn=(0.01, 0.05), wavelength=0.532):
+    """fibres() rendered with torch on `device` (FP32 accumulation): the same
+    random draws and the same point chains and per-axis Gaussian factors, for
+    volumes whose host rendering would take minutes.  Returns a (4, Z, Y, X)
+    float32 tensor on the device."""
+    import torch
+    rng = np.random.default_rng(seed)
+    Z, Y, X = shape
+    vox = np.asarray(voxel, dtype=np.float64)
+    ext = np.array([Z, Y, X]) * vox
+    out = torch.zeros((4, Z * Y * X), dtype=torch.float32, device=device)
+    step = sigma / 2.0
+    half = np.ceil(3 * sigma / vox).astype(int)
+    rel = [torch.arange(-h, h + 1, device=device) for h in half]
+    for _ in range(n):
+        ctrl = rng.uniform(0.0, 1.0, (4, 3)) * ext
+        rho = 2 * math.pi * rng.uniform(*retardance_nm) * 1e-3 / wavelength
+        w = rng.uniform(0.0, math.pi)
+        phase = 2 * math.pi * rng.uniform(*dn) * vox[0] / wavelength
+        vals = (phase, rho * math.cos(2 * w), rho * math.sin(2 * w))
+        dense = _catmull_rom(ctrl, 64)
+        seg = np.linalg.norm(np.diff(dense, axis=0), axis=1)
+        s = np.concatenate([[0.0], np.cumsum(seg)])
+        npts = max(int(s[-1] / step), 2)
+        si = np.linspace(0.0, s[-1], npts)
+        pts_h = np.stack([np.interp(si, s, dense[:, k]) for k in range(3)], -1)
+        ds = s[-1] / (npts - 1)
+        pts = torch.from_numpy(pts_h).to(device)
+        base = torch.from_numpy(np.rint(pts_h / vox).astype(np.int64)).to(device)
+        cell, g, ok = [], [], []
+        for a in range(3):
+            c = base[:, a, None] + rel[a][None, :]
+            g.append(torch.exp(-((c * vox[a] - pts[:, a, None]) ** 2) / (2 * sigma * sigma)))
+            cell.append(c)
+            ok.append((c >= 0) & (c < shape[a]))
+        wgt = (g[0][:, :, None, None] * g[1][:, None, :, None] * g[2][:, None, None, :]
+               * (ds / (math.sqrt(2 * math.pi) * sigma)))
+        flat = (cell[0][:, :, None, None] * Y + cell[1][:, None, :, None]) * X + cell[2][:, None, None, :]
+        keep = ok[0][:, :, None, None] & ok[1][:, None, :, None] & ok[2][:, None, None, :]
+        idx, wk = flat[keep], wgt[keep].to(torch.float32)
+        for j in range(3):
+            out[j].index_add_(0, idx, wk * float(vals[j]))
+    return out.reshape((4,) + tuple(shape))
 
 
 def thin_cells(shape_yx, pixel, n, seed, semi_axes=(0.8, 2.5), phase=(0.1, 0.5),

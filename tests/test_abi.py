@@ -155,8 +155,10 @@ def test_support_and_band_calls_validate_on_the_host(lib):
     # band synthesis: label-free 3D only (unless the support fills the grid)
     thin = api.optics_array(_optics(model=api.MODEL_LABELFREE_THIN))
     assert lib.wo_transfer_function_band(thin, 1, one, one, 1 << 40, None) == -2
+    # the polarisation model's band layout is its reduced form (validated, then the
+    # workspace check fails before any GPU work)
     pol5 = api.optics_array(_optics(model=api.MODEL_POL5_3D, na_det=0.75, ny=128, nx=128))
-    assert lib.wo_transfer_function_band(pol5, 1, one, one, 1 << 40, None) == -2
+    assert lib.wo_transfer_function_band(pol5, 1, one, one, 16, None) == -3
     assert lib.wo_transfer_function_band(arr, 1, None, one, 1 << 40, None) == -1
     assert lib.wo_transfer_function_band(arr, 1, one, one, 16, None) == -3
     # band linear calls: forward, reconstruction or adjoint of a 3D model
@@ -169,3 +171,17 @@ def test_support_and_band_calls_validate_on_the_host(lib):
     assert lib.wo_linear_band(api.OP_RECONSTRUCT, arr, 1, one, one, None, 0.0, one, one, 1 << 40,
                               None) == -2
     assert lib.wo_linear_band(api.OP_ADJOINT, arr, 1, one, one, None, 0.0, one, one, 16, None) == -3
+
+
+def test_pol5_coupling_is_the_oracle_coupling_in_fp32(lib):
+    """wo_pol5_coupling (host only) returns the oracle's kappa rounded to FP32: within
+    one FP32 rounding (the two FP64 evaluations differ by a few FP64 ulps, which can
+    move a value across an FP32 rounding boundary or leave 1e-17 where 0 is exact)."""
+    import numpy as np
+    from oracle import tf as tfm
+    for swing in (0.0, 0.03, 0.1, 0.25):
+        got = api.pol5_coupling(swing).astype(np.complex128)
+        ref = tfm.pol5_coupling(swing)
+        for g, r in ((got.real, ref.real), (got.imag, ref.imag)):
+            assert np.all(np.abs(g - r) <= 2.0 ** -24 * np.abs(r) + 1e-15)
+    assert lib.wo_pol5_coupling(float("nan"), None) == -1

@@ -65,7 +65,6 @@ def test_pol5_64x1024x1024_sampled_and_plane_waves(gpu_lib):
                   na_ill=0.5, na_det=0.75, n_medium=1.33, swing=0.1)
     assert op.hard_edge_margin(o) > 1e-9
     print("[case] pol5 64x1024x1024: TF at sampled frequencies", flush=True)
-    kappa = tfm.pol5_coupling(o.swing)
     tf = gpu_lib.transfer_function([o])          # (1, 5, 4, Z, Y, Xh)
     rng = np.random.default_rng(12)
     samples = [(w[0][0] % Z, w[0][1] % Y, w[0][2] % X) for w in WAVES]
@@ -73,8 +72,7 @@ def test_pol5_64x1024x1024_sampled_and_plane_waves(gpu_lib):
     Hs = {}
     errs = []
     for kz, ky, kx in samples:
-        hp, ha = tfm.labelfree_3d_at(o, kz, ky, kx)
-        H = kappa.real * hp + kappa.imag * ha          # (5, 4)
+        H = tfm.pol5_3d_at(o, kz, ky, kx)              # (5, 4), pinned against the Jones sum
         Hs[(kz, ky, kx)] = H
         if kx <= X // 2:
             got = tf[0, :, :, kz, ky, kx].cpu().numpy()

@@ -112,6 +112,11 @@ CASES = {
     "labelfree_3d_short_transforms": [labelfree(nz=8, ny=256, nx=256, defocus=-0.2, tilt_zenith=0.2,
                                                 edge_width=0.5)],
     "sectors9_short_transforms": [sectors(nz=6, ny=256, nx=256, tilt_zenith=0.15, tilt_azimuth=1.1)],
+    # polarisation bank on a support well inside the grid: synthesised on shortened
+    # transforms as the label-free pair, then mixed by each patch's coupling
+    "pol5_band": [pol5(nz=16, ny=96, nx=128, tilt_zenith=0.2, tilt_azimuth=0.6, edge_width=0.5)],
+    "pol5_band_batch2_swings": [pol5(nz=12, ny=96, nx=96, swing=0.1),
+                                pol5(nz=12, ny=96, nx=96, swing=0.05, defocus=0.3, na_ill=0.3)],
 }
 
 
@@ -294,7 +299,7 @@ def test_band_bank_is_the_full_bank_on_its_support(gpu_lib, torch, name):
 
 
 @pytest.mark.parametrize("name", ["labelfree_3d_band_batch2", "labelfree_3d_short_transforms", "sectors9_band",
-                                  "fluor_cfg1", "pol5"])
+                                  "fluor_cfg1"])
 def test_linear_calls_with_the_band_bank_equal_the_full_bank(gpu_lib, torch, name):
     """wo_linear_band (forward, reconstruction, adjoint) with the band layout cut from
     the full bank gives bit for bit the full-layout calls' results."""
@@ -318,10 +323,78 @@ def test_linear_calls_with_the_band_bank_equal_the_full_bank(gpu_lib, torch, nam
                        gpu_lib.adjoint(opts, full, d))
 
 
-def test_band_synthesis_of_models_without_the_compact_path_is_unsupported(gpu_lib, torch):
-    o = CASES["pol5"][0]
-    sup = gpu_lib.lateral_support([o])
-    if sup["tf_cols"] == o.nx // 2 + 1 and sup["band_rows"] == o.ny:
-        pytest.skip("support fills the grid: the band layout is the full one")
-    with pytest.raises(gpu_lib.WoError):
-        gpu_lib.transfer_function_band([o])
+POL5_BAND = ["pol5", "pol5_ragged", "pol5_band", "pol5_band_batch2_swings", "pol5_aberrated"]
+
+
+def pol5_expand(gpu_lib, opts, red):
+    """The 5 x 4 bank on the support from its reduced form, in plain FP32 on the host:
+    Re(kappa) * H_phase + Im(kappa) * H_abs, each product and the sum rounded alone."""
+    out = []
+    for i, o in enumerate(opts):
+        k = gpu_lib.pol5_coupling(o.swing)
+        u, v = red[i, 0, 0], red[i, 0, 1]
+        kr = k.real.astype(np.float32)[:, :, None, None, None]
+        ki = k.imag.astype(np.float32)[:, :, None, None, None]
+        re = kr * u.real[None, None] + ki * v.real[None, None]
+        im = kr * u.imag[None, None] + ki * v.imag[None, None]
+        out.append((re + 1j * im).astype(np.complex64))
+    return np.stack(out)
+
+
+@pytest.mark.parametrize("name", POL5_BAND)
+def test_pol5_full_bank_is_the_expansion_of_its_reduced_form(gpu_lib, torch, name):
+    """wo_transfer_function_band of the polarisation model is the label-free pair on
+    the support; the full 5 x 4 bank is bit for bit its FP32 expansion there and
+    exactly zero elsewhere; the pair is the oracle's label-free pair."""
+    opts = CASES[name]
+    print(f"[case] pol5 reduced bank {name}", flush=True)
+    sup = gpu_lib.lateral_support(opts)
+    red = gpu_lib.transfer_function_band(opts)
+    assert tuple(red.shape) == (len(opts), 1, 2, opts[0].nz, sup["band_rows"], sup["tf_cols"])
+    full = gpu_lib.transfer_function(opts)
+    cut, rows = band_slice(torch, full, sup, opts[0].ny)
+    redh = red.cpu().numpy()
+    assert np.array_equal(cut.cpu().numpy(), pol5_expand(gpu_lib, opts, redh))
+    rest = full.clone()
+    rest[..., rows, :sup["tf_cols"]] = 0
+    assert int(torch.count_nonzero(rest)) == 0
+    for i, o in enumerate(opts):
+        pair = tfm.labelfree_3d(o)[..., : o.nx // 2 + 1][..., rows, : sup["tf_cols"]]
+        err = rel_l2(redh[i, 0], pair)
+        print(f"  patch {i}: pair rel L2 = {err:.3e}")
+        assert err < TOL_TF
+
+
+@pytest.mark.parametrize("name", POL5_BAND)
+def test_pol5_linear_calls_with_the_reduced_bank_equal_the_full_bank(gpu_lib, torch, name):
+    """wo_linear_band with the reduced polarisation bank (entries formed per
+    frequency in the fused Z pass) gives bit for bit the full-layout calls'
+    results, and the reconstruction is within 1e-4 of the oracle's."""
+    opts = CASES[name]
+    print(f"[case] pol5 reduced linear {name}", flush=True)
+    red = gpu_lib.transfer_function_band(opts)
+    full = gpu_lib.transfer_function(opts)
+    C, P, _, _ = gpu_lib.bank_shape(opts)
+    vol = (opts[0].nz, opts[0].ny, opts[0].nx)
+    g = torch.Generator(device="cuda").manual_seed(11)
+    f = torch.randn((len(opts), P) + vol, device="cuda", generator=g)
+    r = torch.randn((len(opts), C) + vol, device="cuda", generator=g)
+    b = torch.linspace(0.1, 0.2, len(opts) * C, device="cuda").reshape(len(opts), C)
+    assert torch.equal(gpu_lib.linear_band(gpu_lib.OP_FORWARD, opts, red, f, b=b),
+                       gpu_lib.forward(opts, full, f, b=b))
+    assert torch.equal(gpu_lib.linear_band(gpu_lib.OP_ADJOINT, opts, red, r),
+                       gpu_lib.adjoint(opts, full, r))
+    banks = [oracle_bank(o) for o in opts]
+    ds = []
+    for i, o in enumerate(opts):
+        d = linear.forward(banks[i], specimen(o, 500 + i), b[i].cpu().numpy())
+        ds.append((d + synth.gaussian_noise((C,) + vol, 1e-3, 600 + i)).astype(np.float32))
+    dt = torch.from_numpy(np.stack(ds)).cuda()
+    eta = eta_for(opts[0], banks[0])
+    got = gpu_lib.linear_band(gpu_lib.OP_RECONSTRUCT, opts, red, dt, eta=eta, b=b)
+    assert torch.equal(got, gpu_lib.reconstruct(opts, full, dt, eta, b=b))
+    for i in range(len(opts)):
+        ref = linear.reconstruct(banks[i], ds[i], b[i].cpu().numpy().astype(np.float64), eta)
+        err = rel_l2(got[i].cpu().numpy(), ref)
+        print(f"  patch {i}: reconstruction rel L2 = {err:.3e}")
+        assert err < TOL_REC

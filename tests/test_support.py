@@ -78,7 +78,7 @@ def test_support_contains_oracle_bank_and_fields(name):
     assert 2 * bank_x + 1 <= lx <= o0.nx and 2 * bank_y + 1 <= ly <= o0.ny
     assert 2 * (tc - 1) <= lx and fc <= lx
     assert lx in COMPILED + (o0.nx,) and ly in COMPILED + (o0.ny,)
-    if o0.model not in (op.LABELFREE_3D, op.SECTORS9_3D):
+    if o0.model not in (op.LABELFREE_3D, op.SECTORS9_3D, op.POL5_3D):
         assert (ly, lx) == (o0.ny, o0.nx)
     if fc < o0.nx:
         assert 2 * pupil_x + 1 <= fc
