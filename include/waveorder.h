@@ -220,6 +220,23 @@ int wo_pol5_coupling(double swing, float* kappa_out);
 int wo_adjoint(const wo_optics* o, int32_t n, const void* tf, const float* r, float* g_out,
                void* ws, size_t ws_bytes, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation):
+ * wo_reconstruct without a workspace argument.  Its scratch is a static
+ * device array of WO_NOALLOC_SCRATCH_BYTES inside the library, one per GPU,
+ * held until the process ends; the call allocates and frees nothing.  The
+ * caller still passes tf, d, b and f_out as for wo_reconstruct, and the
+ * results are those of wo_reconstruct bit for bit (same kernels and
+ * schedules).  WO_ENOMEM if wo_workspace_size(o, n, WO_OP_RECONSTRUCT)
+ * exceeds WO_NOALLOC_SCRATCH_BYTES; WO_EINVAL if `stream` belongs to another
+ * device than the current one (whose scratch is used).  Every call on one GPU
+ * shares that GPU's array, so calls that overlap in time on one GPU (other
+ * streams, other host threads) race and give undefined results; calls in
+ * order on one stream are safe.  Nothing in the array needs to start at zero:
+ * each call writes every scratch value it reads. */
+#define WO_NOALLOC_SCRATCH_BYTES (64u << 20)
+int wo_reconstruct_noalloc(const wo_optics* o, int32_t n, const void* tf, const float* d,
+                           const float* b, double eta, float* f_out, void* stream);
 
 /* ---------------------------------------------------------------- auto-tune
  * Thin phase-from-defocus model only (WO_MODEL_LABELFREE_THIN).  Parameters

@@ -40,7 +40,7 @@ SYMBOLS = ("wo_bank_shape", "wo_workspace_size", "wo_transfer_function", "wo_for
            "wo_fft_plans_export", "wo_fft_plans_import", "wo_fft_plans_clear", "wo_fft_candidates",
            "wo_tile_grid", "wo_stitch_tiles", "wo_timing_select", "wo_midband_loss_grad_aberration",
            "wo_lateral_support", "wo_transfer_function_band",
-           "wo_linear_band", "wo_pol5_coupling")
+           "wo_linear_band", "wo_reconstruct_noalloc", "wo_pol5_coupling")
 
 _FIELDS = ("model", "nz", "ny", "nx", "dz", "dy", "dx", "wavelength", "na_ill", "na_det",
            "n_medium", "defocus", "tilt_zenith", "tilt_azimuth", "edge_width", "swing")
@@ -124,6 +124,7 @@ def load(path: str = LIB_PATH):
     lib.wo_adjoint.argtypes = [op, i32, vp, vp, vp, vp, sz, vp]
     lib.wo_transfer_function_band.argtypes = [op, i32, vp, vp, sz, vp]
     lib.wo_linear_band.argtypes = [i32, op, i32, vp, vp, vp, ctypes.c_double, vp, vp, sz, vp]
+    lib.wo_reconstruct_noalloc.argtypes = [op, i32, vp, vp, vp, ctypes.c_double, vp, vp]
     lib.wo_pol5_coupling.argtypes = [ctypes.c_double, ctypes.POINTER(ctypes.c_float)]
     lib.wo_strerror.argtypes = [ctypes.c_int]
     lib.wo_strerror.restype = ctypes.c_char_p
@@ -301,6 +302,26 @@ def reconstruct(optics, tf, d, eta, b=None, ws=None, stream=None):
     lib = load()
     return _linear(lib.wo_reconstruct, "wo_reconstruct", optics, tf, d.contiguous(), fshape,
                    lambda out: (_ptr(b), ctypes.c_double(eta), _ptr(out)), ws, stream, OP_RECONSTRUCT)
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20   # WO_NOALLOC_SCRATCH_BYTES
+
+
+def reconstruct_noalloc(optics, tf, d, eta, b=None, out=None, stream=None):
+    """Tikhonov reconstruction with the library's static scratch instead of a
+    workspace (``wo_reconstruct_noalloc``); `out` may be passed to avoid the one
+    allocation this binding would otherwise make (the output)."""
+    import torch
+    lib = load()
+    arr = optics_array(optics)
+    C, P, dims, _ = bank_shape(optics)
+    fshape = (len(arr), P) + _vol(optics)
+    if out is None:
+        out = torch.empty(fshape, dtype=torch.float32, device=d.device)
+    _check(lib.wo_reconstruct_noalloc(arr, len(arr), _ptr(tf), _ptr(d.contiguous()), _ptr(b),
+                                      ctypes.c_double(eta), _ptr(out), _stream(stream)),
+           "wo_reconstruct_noalloc")
+    return out
 
 
 def band_dims(optics):

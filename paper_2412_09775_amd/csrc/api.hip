@@ -1129,7 +1129,9 @@ const char* wo_strerror(int status) {
     case WO_OK: return "ok";
     case WO_EINVAL: return "invalid argument or optics outside the model's validity";
     case WO_EUNSUPPORTED: return "unsupported size or mode";
-    case WO_ENOMEM: return "workspace too small";
+    case WO_ENOMEM:
+      return "workspace too small (below wo_workspace_size(), or beyond the static scratch of "
+             "wo_reconstruct_noalloc)";
     case WO_EHIP: return "HIP runtime error";
     case WO_EALIAS: return "transfer-function support exceeds the sampled band";
     default: return "unknown status";
@@ -1400,7 +1402,64 @@ int wo_adjoint(const wo_optics* o, int32_t n, const void* tf, const float* r, fl
 
 }  // extern "C"
 
+// ---------------------------------------------------------------- reconstruction without allocation
+//
+// Scratch of wo_reconstruct_noalloc: one copy of this array per GPU, held until
+// the process ends.  In host code `scratch` names a host-side stand-in, not a
+// device address; the device address comes from hipGetSymbolAddress, taken
+// once per device with that device current, and only that address is used.
+static __device__ __align__(256) unsigned char scratch[WO_NOALLOC_SCRATCH_BYTES];
 
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxDevices] = {};
+
+// Device address of the current device's scratch (resolved on its first use).
+int scratch_address(void** out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return WO_EHIP;
+  if (dev < 0 || dev >= kMaxDevices) return WO_EUNSUPPORTED;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return WO_EHIP;
+    g_scratch_dev[dev] = p;
+  }
+  *out = g_scratch_dev[dev];
+  return WO_OK;
+}
+}  // namespace
+
+extern "C" int wo_reconstruct_noalloc(const wo_optics* o, int32_t n, const void* tf, const float* d,
+                                      const float* b, double eta, float* f_out, void* stream) {
+  if (!o || n < 1) return WO_EINVAL;
+  int st = check_sampling(o);
+  if (st) return st;
+  for (int i = 1; i < n; ++i)
+    if (!same_sampling(&o[0], &o[i])) return WO_EINVAL;
+  if (!tf || !d || !f_out) return WO_EINVAL;
+  if (!(eta >= 0.0) || !isfinite(eta)) return WO_EINVAL;
+  Shape s;
+  bank_shape(o, &s);
+  if (s.P != 1 && s.P != 2 && s.P != 4) return WO_EUNSUPPORTED;
+  if (!s.thin && !zop_fits((int)s.Z, std::max(s.C, s.P))) return WO_EUNSUPPORTED;
+  if (eta == 0.0 && s.P != 1) return WO_EUNSUPPORTED;
+  if (linear_ws(n, s) > (size_t)WO_NOALLOC_SCRATCH_BYTES) return WO_ENOMEM;
+  // the stream must run on the current device, whose scratch is used
+  hipStream_t hs = (hipStream_t)stream;
+  if (hs) {
+    int cur = 0;
+    hipDevice_t sdev = 0;
+    if (hipGetDevice(&cur) != hipSuccess || hipStreamGetDevice(hs, &sdev) != hipSuccess) return WO_EHIP;
+    if ((int)sdev != cur) return WO_EINVAL;
+  }
+  void* ws = nullptr;
+  st = scratch_address(&ws);
+  if (st) return st;
+  // the linear pipeline writes every scratch value it reads: nothing to clear
+  return run_linear(o, n, s, (const float2*)tf, d, f_out, b, kModeSolve, (float)eta, ws, hs);
+}
 
 extern "C" {
 

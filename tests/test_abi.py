@@ -173,6 +173,20 @@ def test_support_and_band_calls_validate_on_the_host(lib):
     assert lib.wo_linear_band(api.OP_ADJOINT, arr, 1, one, one, None, 0.0, one, one, 16, None) == -3
 
 
+def test_noalloc_reconstruction_validates_on_the_host(lib):
+    """wo_reconstruct_noalloc rejects inputs whose scratch would exceed the static
+    array, and bad arguments, before any GPU work (fake pointers never touched)."""
+    one = ctypes.c_void_p(1)
+    big = api.optics_array(_optics(nz=96, ny=512, nx=512))
+    assert api.workspace_size(_optics(nz=96, ny=512, nx=512), api.OP_RECONSTRUCT) > api.NOALLOC_SCRATCH_BYTES
+    assert lib.wo_reconstruct_noalloc(big, 1, one, one, None, 1e-3, one, None) == -3
+    arr = api.optics_array(_optics())
+    assert lib.wo_reconstruct_noalloc(arr, 1, None, one, None, 1e-3, one, None) == -1
+    assert lib.wo_reconstruct_noalloc(arr, 1, one, one, None, -1.0, one, None) == -1
+    assert lib.wo_reconstruct_noalloc(arr, 1, one, one, None, 0.0, one, None) == -2   # P = 2 needs eta > 0
+    assert lib.wo_reconstruct_noalloc(arr, 0, one, one, None, 1e-3, one, None) == -1
+
+
 def test_pol5_coupling_is_the_oracle_coupling_in_fp32(lib):
     """wo_pol5_coupling (host only) returns the oracle's kappa rounded to FP32: within
     one FP32 rounding (the two FP64 evaluations differ by a few FP64 ulps, which can
