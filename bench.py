@@ -1,18 +1,26 @@
 """Throughput of the WaveOrder hot path on one MI355X.
 
-Workload: label-free absorption + phase from a brightfield stack,
-96 x 512 x 512 voxels (dz 0.2 um, dx = dy 0.1 um), lambda0 0.532 um, NA_ill
-0.5, NA_det 1.2, n 1.33; 1 channel -> 2 properties; 200 random ellipsoids,
-Poisson-Gaussian noise.  One step is the whole reconstruction hot path on
-that volume: transfer-function synthesis (pupils, propagators, correlation,
-3D transforms) followed by the Tikhonov reconstruction (forward 3D FFT,
-per-frequency solve fused with the Z transform, inverse 3D FFT).  Inputs are
-resident in HBM before timing starts.
+Headline workload: polarisation-resolved label-free reconstruction, 5 channels
+(swing 0.1) x 4 properties (phase, rho cos 2w, rho sin 2w, absorption) on a
+64 x 1024 x 1024 grid (dz 0.25 um, dx = dy 0.1 um), lambda0 0.532 um, NA_ill
+0.5, NA_det 0.75, n 1.33; 300 random spline fibres, Gaussian noise.  One step
+is the whole reconstruction hot path on that volume: transfer-function
+synthesis (pupils, propagators, correlation, 3D transforms; the 5 x 4 bank in
+its reduced form, the label-free pair on its lateral support) followed by the
+Tikhonov reconstruction (forward 3D FFT of the 5 channels, per-frequency 5 x 4
+solve fused with the Z transform, inverse 3D FFT of the 4 properties).
+Inputs are resident in HBM before timing starts.
 
-Prints one JSON line.  `value` = reconstructed voxels per second for the step
-above; extra fields give the rate with a cached transfer function, each
-kernel's time and algorithmic bytes, the roofline of the dominant kernel and
-the FP64 oracle timed on a bounded sample on the host.
+Secondary workloads with the same measurements: label-free phase and
+absorption, 96 x 512 x 512, 1 channel -> 2 properties; widefield fluorescence,
+32 x 64 x 64, 1 -> 1.  Every workload's timed output is compared with the FP64
+oracle (the whole volume where the oracle can reconstruct it in seconds,
+sampled frequencies at 64 x 1024 x 1024).
+
+Prints one JSON line.  `value` = reconstructed voxels per second of the
+headline step; extra fields give the rate with a cached transfer function,
+each kernel's time and algorithmic bytes, the roofline of the dominant kernel,
+the parity check and the FP64 oracle timed on a bounded sample on the host.
 """
 
 from __future__ import annotations
@@ -30,18 +38,44 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-WORKLOAD = dict(model=1, nz=96, ny=512, nx=512, dz=0.2, dy=0.1, dx=0.1, wavelength=0.532,
-                na_ill=0.5, na_det=1.2, n_medium=1.33, defocus=0.0, tilt_zenith=0.0,
-                tilt_azimuth=0.0, edge_width=0.0, swing=0.1)
+_OPT = dict(defocus=0.0, tilt_zenith=0.0, tilt_azimuth=0.0, edge_width=0.0, swing=0.1)
+# polarisation-resolved 5 x 4, the headline workload
+POL5 = dict(_OPT, model=3, nz=64, ny=1024, nx=1024, dz=0.25, dy=0.1, dx=0.1, wavelength=0.532,
+            na_ill=0.5, na_det=0.75, n_medium=1.33)
+# label-free phase and absorption, 1 x 2
+LABELFREE = dict(_OPT, model=1, nz=96, ny=512, nx=512, dz=0.2, dy=0.1, dx=0.1, wavelength=0.532,
+                 na_ill=0.5, na_det=1.2, n_medium=1.33)
+# widefield fluorescence, 1 x 1
+FLUOR = dict(_OPT, model=0, nz=32, ny=64, nx=64, dz=0.25, dy=0.1, dx=0.1, wavelength=0.52, na_ill=0.0,
+             na_det=1.2, n_medium=1.33)
+WORKLOAD = LABELFREE          # the 3D label-free sampling the extra sections reuse
 ETA_REL = 1e-3
+TOL_REC = 1e-4                # reconstruction parity (relative L2) vs the FP64 oracle
+
+SECTIONS = {
+    "pol5": dict(optics=POL5, name="pol5_64x1024x1024",
+                 workload="polarisation-resolved label-free, 64x1024x1024, 5 channels (swing 0.1) x 4 "
+                          "properties, 300 spline fibres + N(0, 1e-3^2) noise; bank in reduced form "
+                          "(label-free pair on its lateral support)"),
+    "labelfree": dict(optics=LABELFREE, name="labelfree3d_96x512x512",
+                      workload="label-free 3D phase+absorption, 96x512x512, 1 channel x 2 properties, "
+                               "200 ellipsoids + Poisson-Gaussian noise (bank kept on its lateral "
+                               "support)"),
+    "fluor": dict(optics=FLUOR, name="fluor3d_32x64x64",
+                  workload="widefield fluorescence, 32x64x64, 1 x 1, 50 beads + N(0, 1e-3^2) noise, "
+                           "eta 1e-3 (full-layout calls)"),
+}
 
 
-def kernel_bytes(name, Z, Y, X, sup, C=1, P=2):
-    """Algorithmic HBM bytes one launch of each kernel must move in this step.
+def kernel_bytes(name, Z, Y, X, sup, C=1, P=2, E=None):
+    """Algorithmic HBM bytes one launch of each kernel must move in the step.
 
     sup: the lateral support (wo_lateral_support): the fields A and B are kept on
     field_cols columns at ly points along y, the bank and the spectra on the
-    columns k < kt of every row (of the band rows once transformed along Y)."""
+    columns k < kt of every row (of the band rows once transformed along Y).
+    C, P: channels and properties; E: transfer-function values read per
+    frequency by the fused Z pass (C * P, or 2 for the reduced 5 x 4 bank)."""
+    E = C * P if E is None else E
     fa, fb = sup["field_cols"]
     kt, nb, (ly, _) = sup["tf_cols"], sup["band_rows"], sup["tf_lengths"]
     Xh = X // 2 + 1
@@ -54,10 +88,10 @@ def kernel_bytes(name, Z, Y, X, sup, C=1, P=2):
         # reconstruction
         "k_rows_r2c": C * (4 * full + cplx * rows_kt),
         "k_cols_y_fwd": C * cplx * (rows_kt + band),
-        f"k_zop<{P}>": cplx * band * (C + C * P + P),
+        f"k_zop<{P}>": cplx * band * (C + E + P),
         "k_cols_y_inv": P * cplx * (band + rows_kt),
         "k_rows_c2r": P * (cplx * rows_kt + 4 * full),
-        # transfer-function synthesis
+        # transfer-function synthesis (the label-free pair)
         "k_tf_fields_y": cplx * Z * ly * (fa + fb),
         "k_tf_rows_lf": cplx * Z * ly * (fa + fb) + 2 * cplx * tf_rows,
         "k_cols_y_tf": 2 * cplx * (tf_rows + band),
@@ -69,17 +103,24 @@ def kernel_bytes(name, Z, Y, X, sup, C=1, P=2):
     return table.get(name)
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "labelfree3d_96x512x512_hbm_traffic.txt")
 CSRC = os.path.join(ROOT, "paper_2412_09775_amd", "csrc")
-# kernel name in the library's timing report -> symbol in the counter summary (the
-# column passes share one symbol across launches and are not listed); the TF
-# kernels are compiled for the synthesis' transform lengths (ly, lx)
-def counter_symbols(sup):
+
+
+def traffic_file(section):
+    return os.path.join(ROOT, "profiles", f"{SECTIONS[section]['name']}_hbm_traffic.txt")
+
+
+def counter_symbols(sup, Z, X, P, C):
+    """Kernel name in the library's timing report -> symbol in the counter summary
+    (the column passes share one symbol across launches and are not listed); the
+    TF kernels are compiled for the synthesis' transform lengths (ly, lx)."""
     ly, lx = sup["tf_lengths"]
-    return {"k_zop<2>": "wo::k_zop<2, 1, 96>", "k_rows_r2c": "wo::k_rows_r2c<512>",
-            "k_rows_c2r": "wo::k_rows_c2r<512>", "k_tf_rows_lf": f"wo::k_tf_rows_lf<{lx}>",
+    ct = 1 if C == 1 else (5 if C == 5 else 0)
+    zop = f"wo::k_zop<{P}, {ct}, {Z}, true>" if C == 5 and P == 4 else f"wo::k_zop<{P}, {ct}, {Z}, false>"
+    return {f"k_zop<{P}>": zop, "k_rows_r2c": f"wo::k_rows_r2c<{X}>",
+            "k_rows_c2r": f"wo::k_rows_c2r<{X}>", "k_tf_rows_lf": f"wo::k_tf_rows_lf<{lx}>",
             "k_tf_fields_y": f"wo::k_tf_fields_y<{ly}, 2, false>",
-            "k_cols_expand": "wo::k_cols_expand<96, 16>"}
+            "k_cols_z_band": f"wo::k_cols_expand<{Z}, {min(16, 8192 // Z)}>"}
 
 
 def source_sha1():
@@ -93,18 +134,17 @@ def source_sha1():
     return h.hexdigest()
 
 
-def measured_traffic(kernel, sup):
+def measured_traffic(section, kernel, symbols):
     """HBM bytes per launch from the committed FETCH_SIZE/WRITE_SIZE summary, or None
     when the kernel sources changed since the counters were taken."""
-    names = counter_symbols(sup)
     try:
-        lines = open(TRAFFIC_FILE).read().splitlines()
+        lines = open(traffic_file(section)).read().splitlines()
     except OSError:
         return None
     rec = [ln.split()[1] for ln in lines if ln.startswith("source_sha1")]
-    if not rec or rec[0] != source_sha1() or kernel not in names:
+    if not rec or rec[0] != source_sha1() or kernel not in symbols:
         return None
-    want = names[kernel]
+    want = symbols[kernel]
     best = None
     for ln in lines:
         f = ln.split("\t")
@@ -119,7 +159,7 @@ def _symbol(name):
     return name.split("(")[0]
 
 
-def summarise_trace(trace_dir, command):
+def summarise_trace(trace_dir, command, title):
     """Per (kernel, grid) call count and average duration from a rocprofv3
     --kernel-trace CSV directory, as the text committed under profiles/."""
     import csv
@@ -131,8 +171,7 @@ def summarise_trace(trace_dir, command):
         d = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-3
         c, t = agg.get(k, (0, 0.0))
         agg[k] = (c + 1, t + d)
-    out = ["# Kernel durations: label-free 3D, 96x512x512, 1 channel x 2 properties "
-           "(TF synthesis + reconstruction)",
+    out = [f"# Kernel durations: {title}",
            f"# command: {command}",
            f"source_sha1 {source_sha1()}",
            "kernel\tgrid\tcalls\tavg_us\ttotal_us"]
@@ -141,7 +180,7 @@ def summarise_trace(trace_dir, command):
     return "\n".join(out) + "\n"
 
 
-def summarise_counters(fetch_dir, write_dir, commands):
+def summarise_counters(fetch_dir, write_dir, commands, title):
     """Per-dispatch FETCH_SIZE and WRITE_SIZE (KiB) of every kernel, scaled by what the
     counters read for the 1 GiB device copy in the same run, in MB per dispatch."""
     import csv
@@ -171,8 +210,7 @@ def summarise_counters(fetch_dir, write_dir, commands):
         seq_f[fe[i][:2]].append(fe[i][2])
     for i in sorted(wr):
         seq_w[wr[i][:2]].append(wr[i][2])
-    out = ["# HBM traffic per dispatch: label-free 3D, 96x512x512 (same workload as the kernel "
-           "durations)"]
+    out = [f"# HBM traffic per dispatch: {title} (same workload as the kernel durations)"]
     out += [f"# command: {c}" for c in commands]
     out += [f"# calibration: 1 GiB device copy reads FETCH_SIZE={cf:.1f} KiB, "
             f"WRITE_SIZE={cw:.1f} KiB",
@@ -189,116 +227,193 @@ def summarise_counters(fetch_dir, write_dir, commands):
     return "\n".join(out) + "\n"
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-nz", type=int, default=96)
-    ap.add_argument("--no-autotune", action="store_true")
-    ap.add_argument("--tune-patches", type=int, default=256)
-    ap.add_argument("--tune-iters", type=int, default=100)
-    ap.add_argument("--cnn-train-patches", type=int, default=16384)
-    ap.add_argument("--cnn-epochs", type=int, default=8)
-    ap.add_argument("--cnn-tune-iters", type=int, default=20)
-    ap.add_argument("--restore-tiles", type=int, default=64)
-    ap.add_argument("--fov-size", type=int, default=2048, help="field of view side (0: skip)")
-    ap.add_argument("--no-multi-aperture", action="store_true")
-    ap.add_argument("--no-aberration", action="store_true")
-    ap.add_argument("--main-only", action="store_true",
-                    help="skip the full-layout comparison (profiled runs: only the bench step's "
-                         "kernels in the trace)")
-    ap.add_argument("--no-fft-tune", action="store_true", help="keep the default FFT schedules")
-    ap.add_argument("--fft-plans", default="", help="import an FFT schedule table instead of tuning")
-    ap.add_argument("--save-fft-plans", default="", help="write the FFT schedule table used")
-    ap.add_argument("--restore-graph", type=int, default=2, choices=(0, 1, 2),
-                    help="graph mode of the CNN-started restoration (multistart uses 1)")
-    ap.add_argument("--calibrate-copy", action="store_true",
-                    help="also run a plain 1 GiB device copy (reference for HBM counters)")
-    ap.add_argument("--summarise-trace", default="", help="(no GPU) write the kernel-duration "
-                    "summary of a rocprofv3 --kernel-trace directory to --summary-out")
-    ap.add_argument("--summarise-counters", nargs=2, default=None, metavar=("FETCH_DIR", "WRITE_DIR"),
-                    help="(no GPU) write the FETCH_SIZE/WRITE_SIZE summary to --summary-out")
-    ap.add_argument("--summary-command", action="append", default=[],
-                    help="command line recorded in the summary header (repeatable)")
-    ap.add_argument("--summary-out", default="")
-    args = ap.parse_args()
-    if args.summarise_trace or args.summarise_counters:
-        text = (summarise_trace(args.summarise_trace, " ".join(args.summary_command))
-                if args.summarise_trace else
-                summarise_counters(*args.summarise_counters, args.summary_command))
-        if args.summary_out:
-            open(args.summary_out, "w").write(text)
-        else:
-            sys.stdout.write(text)
-        return
-    if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus above 1 is not supported"}))
-        sys.exit(2)
+# ---------------------------------------------------------------- inputs
 
-    import torch
+def pol5_sigma_max_sq(api, torch, o, red):
+    """max over frequencies of sigma_max(H(nu))^2 for the 5 x 4 bank formed from its
+    reduced form red (1, 1, 2, Z, rows, cols): per frequency the largest eigenvalue
+    of the 4 x 4 Gram matrix H^H H by power iteration (elementwise torch ops)."""
+    k = torch.from_numpy(api.pol5_coupling(o.swing)).to(red.device)      # (5, 4) complex64
+    u, v = red[0, 0, 0].reshape(-1), red[0, 0, 1].reshape(-1)
+    best = 0.0
+    for s in range(0, u.numel(), 1 << 22):
+        uu, vv = u[s:s + (1 << 22)], v[s:s + (1 << 22)]
+        H = [[k[c, p].real * uu + k[c, p].imag * vv for p in range(4)] for c in range(5)]
+        G = [[sum(H[c][p].conj() * H[c][q] for c in range(5)) for q in range(4)] for p in range(4)]
+        x = [torch.ones_like(uu) for _ in range(4)]
+        lam = None
+        for _ in range(60):
+            y = [sum(G[p][q] * x[q] for q in range(4)) for p in range(4)]
+            nrm = torch.sqrt(sum((t.abs() ** 2) for t in y)) + 1e-30
+            x = [t / nrm for t in y]
+            lam = nrm
+        best = max(best, float(lam.max()))
+    return best
 
+
+def make_inputs(api, torch, dev, key, o, sup):
+    """The workload's synthetic data on the device (forward model of a seeded
+    specimen through the GPU bank, plus noise) and eta.  Returns (d, eta, band)."""
     import synth
-    from paper_2412_09775_amd import api
+    Z, Y, X = o.nz, o.ny, o.nx
+    band = key != "fluor"
+    tf = api.transfer_function_band([o], device=dev) if band else api.transfer_function([o], device=dev)
+    lin = ((lambda op, x: api.linear_band(op, [o], tf, x)) if band else
+           (lambda op, x: api.forward([o], tf, x)))
+    if key == "pol5":
+        f = synth.fibres_on_device((Z, Y, X), (o.dz, o.dy, o.dx), 300, seed=3001, device=dev)[None]
+        d = lin(api.OP_FORWARD, f)
+        del f
+        api.add_gaussian_noise(d, 1e-3, 3002)
+        eta = ETA_REL * pol5_sigma_max_sq(api, torch, o, tf)
+    elif key == "labelfree":
+        obj = synth.ellipsoids((Z, Y, X), (o.dz, o.dy, o.dx), 200, seed=2001)
+        clean = lin(api.OP_FORWARD, torch.from_numpy(obj[None]).to(dev))
+        d = torch.from_numpy(synth.poisson_gaussian(clean.cpu().numpy(), seed=2002)).to(dev)
+        # 1 channel: sigma_max^2 = |H_phase|^2 + |H_abs|^2
+        eta = ETA_REL * float((tf.abs() ** 2).sum(dim=2).max())
+    else:
+        obj = synth.beads((Z, Y, X), 50, seed=1001)[None]
+        clean = lin(api.OP_FORWARD, torch.from_numpy(obj[None]).to(dev))
+        d = clean + torch.from_numpy(synth.gaussian_noise((1, 1, Z, Y, X), 1e-3, 1002).astype(np.float32)).to(dev)
+        eta = 1e-3
+    torch.cuda.synchronize()
+    return d.contiguous(), eta, band
 
-    api.load()
-    dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
-    o = api.Optics(**WORKLOAD)
+
+# ---------------------------------------------------------------- parity of the timed output
+
+def _oracle_optics(o):
+    from oracle import optics as op
+    return op.Optics(model=o.model, nz=o.nz, ny=o.ny, nx=o.nx, dz=o.dz, dy=o.dy, dx=o.dx,
+                     wavelength=o.wavelength, na_ill=o.na_ill, na_det=o.na_det, n_medium=o.n_medium,
+                     swing=o.swing)
+
+
+def parity_full(o, d_host, f_gpu, eta):
+    """FP64 oracle TF synthesis + reconstruction of the bench's own data, element by
+    element against the timed GPU output (relative L2 over the whole volume)."""
+    import scipy.fft as sfft
+
+    from oracle import linear
+    from oracle import tf as tfm
+    t0 = time.perf_counter()
+    with sfft.set_workers(len(os.sched_getaffinity(0))):
+        bank = tfm.transfer_function(_oracle_optics(o))
+        ref = linear.reconstruct(bank, d_host.astype(np.float64), None, eta)
+    err = float(np.linalg.norm(f_gpu.astype(np.float64) - ref) / np.linalg.norm(ref))
+    return {"kind": "whole volume", "oracle": "oracle.tf.transfer_function + oracle.linear.reconstruct (FP64)",
+            "rel_l2": err, "tolerance": TOL_REC, "ok": bool(err < TOL_REC),
+            "oracle_seconds": round(time.perf_counter() - t0, 1)}
+
+
+def _dft_at(vol, freqs):
+    """Direct DFT of vol (C, Z, Y, X) at frequency indices [(kz, ky, kx)], FP64:
+    per plane, the X sum by a product with exp(-i 2 pi kx x / X), then Y, then Z."""
+    C, Z, Y, X = vol.shape
+    kz = np.array([f[0] for f in freqs])
+    ky = np.array([f[1] for f in freqs])
+    kx = np.array([f[2] for f in freqs])
+    ex = np.exp(-2j * np.pi * np.outer(np.arange(X), kx) / X)          # (X, K)
+    ey = np.exp(-2j * np.pi * np.outer(ky, np.arange(Y)) / Y)          # (K, Y)
+    ez = np.exp(-2j * np.pi * np.outer(np.arange(Z), kz) / Z)          # (Z, K)
+    out = np.zeros((C, len(freqs)), dtype=np.complex128)
+    for z in range(Z):
+        pl = vol[:, z].astype(np.float64)                               # (C, Y, X)
+        tx = pl @ ex                                                    # (C, Y, K)
+        t = np.einsum("ky,cyk->ck", ey, tx)
+        out += t * ez[z][None, :]
+    return out
+
+
+def parity_pol5_sampled(o, d_host, f_gpu, eta, sup, n=12, seed=3003):
+    """At sampled frequencies of the support: the oracle's per-frequency Tikhonov
+    solve F = (H^H H + eta I)^-1 H^H D with H from the direct source sum
+    (oracle.tf.pol5_3d_at) and D the direct DFT of the bench's own data, against the
+    direct DFT of the timed GPU output there (relative L2 over the samples).  The
+    whole-volume FP64 solve does not fit the bench's time."""
+    from oracle import tf as tfm
+    t0 = time.perf_counter()
+    oo = _oracle_optics(o)
+    rng = np.random.default_rng(seed)
+    ky_max = (sup["band_rows"] - 1) // 2
+    kt = sup["tf_cols"]
+    freqs = []
+    while len(freqs) < n:
+        # in-band frequencies: low and moderate axial and lateral indices
+        kz = int(rng.integers(-4, 5)) % o.nz
+        ky = int(rng.integers(-ky_max // 2, ky_max // 2 + 1)) % o.ny
+        kx = int(rng.integers(1, kt // 2))
+        if (kz, ky, kx) not in freqs:
+            freqs.append((kz, ky, kx))
+    Dg = _dft_at(d_host, freqs)                                          # (5, K)
+    Fg = _dft_at(f_gpu, freqs)                                           # (4, K)
+    num = den = 0.0
+    for k, (kz, ky, kx) in enumerate(freqs):
+        H = tfm.pol5_3d_at(oo, kz, ky, kx)
+        Hh = H.conj().T
+        F = np.linalg.solve(Hh @ H + eta * np.eye(4), Hh @ Dg[:, k])
+        num += float(np.sum(np.abs(Fg[:, k] - F) ** 2))
+        den += float(np.sum(np.abs(F) ** 2))
+    err = math.sqrt(num / den)
+    return {"kind": f"{n} sampled frequencies of the support",
+            "oracle": "oracle.tf.pol5_3d_at (direct source sum) + per-frequency solve; direct DFTs (FP64)",
+            "rel_l2": err, "tolerance": TOL_REC, "ok": bool(err < TOL_REC),
+            "oracle_seconds": round(time.perf_counter() - t0, 1)}
+
+
+# ---------------------------------------------------------------- one linear workload
+
+def linear_section(api, torch, dev, args, key, parity=True):
+    """Step = TF synthesis + reconstruction of the workload, timed; per-kernel
+    table, dominant-kernel roofline, cached-TF rate and the parity of the timed
+    output against the oracle."""
+    spec = SECTIONS[key]
+    o = api.Optics(**spec["optics"])
     Z, Y, X = o.nz, o.ny, o.nx
     V = Z * Y * X
+    C, P, _, _ = api.bank_shape([o])
     sup = api.lateral_support([o])
-
-    # ---- inputs (untimed): specimen, forward model on the GPU, noise on the host
-    t0 = time.time()
-    obj = synth.ellipsoids((Z, Y, X), (o.dz, o.dy, o.dx), 200, seed=2001)
-    print(f"[bench] specimen generated in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
-    tf = api.transfer_function([o], device=dev)
-    clean = api.forward([o], tf, torch.from_numpy(obj[None]).to(dev))
-    noisy = synth.poisson_gaussian(clean.cpu().numpy(), seed=2002)
-    d = torch.from_numpy(noisy).to(dev)
-    # eta relative to the largest |H|^2 (1 channel: sigma_max^2 = |H_phase|^2 + |H_abs|^2)
-    smax2 = float((tf.abs() ** 2).sum(dim=2).max())
-    eta = ETA_REL * smax2
-    ws_tf = torch.empty(api.workspace_size([o], api.OP_TRANSFER_FUNCTION), dtype=torch.uint8, device=dev)
-    ws_rec = torch.empty(api.workspace_size([o], api.OP_RECONSTRUCT), dtype=torch.uint8, device=dev)
-    tf_buf = tf.clone()
+    d, eta, band = make_inputs(api, torch, dev, key, o, sup)
+    print(f"[bench] {key}: inputs ready (eta {eta:.3e})", file=sys.stderr, flush=True)
     lib = api.load()
     arr = api.optics_array([o])
-    fout = torch.empty((1, 2, Z, Y, X), dtype=torch.float32, device=dev)
     stream = torch.cuda.current_stream()
     sp = api._stream(stream)
-
-    # The step keeps the bank on its lateral support (band layout: the values off
-    # it are zero and implied, like the Hermitian half); the full-layout bank is
-    # timed as a secondary figure.
-    tf_band = torch.empty(api.band_dims([o]), dtype=torch.complex64, device=dev)
+    ws_tf = torch.empty(api.workspace_size([o], api.OP_TRANSFER_FUNCTION), dtype=torch.uint8, device=dev)
+    ws_rec = torch.empty(api.workspace_size([o], api.OP_RECONSTRUCT), dtype=torch.uint8, device=dev)
+    fout = torch.empty((1, P, Z, Y, X), dtype=torch.float32, device=dev)
+    bank = torch.empty(api.band_dims([o]) if band else api.bank_dims([o]), dtype=torch.complex64, device=dev)
 
     def step_tf():
-        st = lib.wo_transfer_function_band(arr, 1, api._ptr(tf_band), api._ptr(ws_tf), ws_tf.numel(), sp)
+        fn = lib.wo_transfer_function_band if band else lib.wo_transfer_function
+        st = fn(arr, 1, api._ptr(bank), api._ptr(ws_tf), ws_tf.numel(), sp)
         assert st == 0, st
 
-    def step_rec(bank):
-        st = lib.wo_linear_band(api.OP_RECONSTRUCT, arr, 1, api._ptr(bank), api._ptr(d), None, eta,
-                                api._ptr(fout), api._ptr(ws_rec), ws_rec.numel(), sp)
-        assert st == 0, st
-
-    def full_layout_step():
-        st = lib.wo_transfer_function(arr, 1, api._ptr(tf_buf), api._ptr(ws_tf), ws_tf.numel(), sp)
-        assert st == 0, st
-        st = lib.wo_reconstruct(arr, 1, api._ptr(tf_buf), api._ptr(d), None, eta, api._ptr(fout),
-                                api._ptr(ws_rec), ws_rec.numel(), sp)
+    def step_rec():
+        if band:
+            st = lib.wo_linear_band(api.OP_RECONSTRUCT, arr, 1, api._ptr(bank), api._ptr(d), None, eta,
+                                    api._ptr(fout), api._ptr(ws_rec), ws_rec.numel(), sp)
+        else:
+            st = lib.wo_reconstruct(arr, 1, api._ptr(bank), api._ptr(d), None, eta, api._ptr(fout),
+                                    api._ptr(ws_rec), ws_rec.numel(), sp)
         assert st == 0, st
 
     def full_step():
         step_tf()
-        step_rec(tf_band)
+        step_rec()
+
+    def timed(fn, k):
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        for _ in range(k):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - a) * 1e3 / k
 
     for _ in range(args.warmup):
         full_step()
     torch.cuda.synchronize()
-    print("[bench] warmup done", file=sys.stderr, flush=True)
 
     # ---- FFT schedules: the library's defaults, then the tuner's picks (or a saved table)
     tuner = {}
@@ -306,40 +421,32 @@ def main():
         api.fft_plans_import(open(args.fft_plans).read())
         tuner["imported"] = os.path.basename(args.fft_plans)
     elif not args.no_fft_tune:
-        torch.cuda.synchronize()
+        before = api.fft_plans_export()
+        tuner["ms_per_step_default_schedules"] = timed(full_step, args.steps)
         a = time.perf_counter()
-        for _ in range(args.steps):
-            full_step()
-        torch.cuda.synchronize()
-        tuner["ms_per_step_default_schedules"] = (time.perf_counter() - a) * 1e3 / args.steps
-        a = time.perf_counter()
-        api.fft_tune(api.OP_TRANSFER_FUNCTION, [o], out=tf_buf, reps=15, ws=ws_tf, stream=stream)
-        api.fft_tune(api.OP_RECONSTRUCT, [o], tf=tf_buf, x=d, out=fout, eta=eta, reps=15, ws=ws_rec,
-                     stream=stream)
+        tf_out = torch.empty_like(bank)
+        api.fft_tune(api.OP_TRANSFER_FUNCTION, [o], out=tf_out, reps=15, ws=ws_tf, stream=stream, band=band)
+        del tf_out
+        step_tf()
+        api.fft_tune(api.OP_RECONSTRUCT, [o], tf=bank, x=d, out=fout, eta=eta, reps=15, ws=ws_rec,
+                     stream=stream, band=band)
         tuner["tune_s"] = round(time.perf_counter() - a, 3)
         for _ in range(args.warmup):
             full_step()
-        torch.cuda.synchronize()
-        # The tuner judges each call on its own; the step runs the two calls
-        # back to back (other cache contents), so keep its table only if the
-        # step is faster with it.
-        a = time.perf_counter()
-        for _ in range(args.steps):
-            full_step()
-        torch.cuda.synchronize()
-        tuner["ms_per_step_tuned_schedules"] = (time.perf_counter() - a) * 1e3 / args.steps
+        # The tuner judges each call on its own; the step runs the two calls back
+        # to back (other cache contents), so keep its picks only if the step is
+        # faster with them.
+        tuner["ms_per_step_tuned_schedules"] = timed(full_step, args.steps)
         if tuner["ms_per_step_tuned_schedules"] >= tuner["ms_per_step_default_schedules"]:
-            tuner["tuned_table_dropped"] = api.fft_plans_export().splitlines()
+            mine = [ln for ln in api.fft_plans_export().splitlines() if ln not in before.splitlines()]
+            tuner["tuned_table_dropped"] = mine
             api.fft_plans_clear()
+            if before:
+                api.fft_plans_import(before)
             for _ in range(args.warmup):
                 full_step()
-            torch.cuda.synchronize()
-    if args.save_fft_plans:
-        os.makedirs(os.path.dirname(os.path.abspath(args.save_fft_plans)), exist_ok=True)
-        with open(args.save_fft_plans, "w") as fh:
-            fh.write(api.fft_plans_export())
     tuner["table"] = api.fft_plans_export().splitlines()
-    print(f"[bench] fft schedules: {tuner}", file=sys.stderr, flush=True)
+    print(f"[bench] {key}: fft schedules {tuner}", file=sys.stderr, flush=True)
 
     # ---- per-kernel pass: K steps with every library kernel bracketed by HIP events
     # (the events add gaps between launches, so this pass is not the timed one)
@@ -355,81 +462,162 @@ def main():
     # the dominant kernel only (its duration for the roofline)
     api.timing_select(dom)
     api.timing_enable(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        full_step()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
+    ms = timed(full_step, args.steps)
     api.timing_enable(False)
     dom_rec = api.timing_report()[dom]
     api.timing_select(None)
-    ms = (t1 - t0) * 1e3 / args.steps
-    value = V / (ms * 1e-3)
+    f_timed = fout.cpu().numpy()[0]
 
-    # ---- cached-TF reconstruction rate (secondary)
-    torch.cuda.synchronize()
-    r0 = time.perf_counter()
-    for _ in range(args.steps):
-        step_rec(tf_band)
-    torch.cuda.synchronize()
-    ms_rec = (time.perf_counter() - r0) * 1e3 / args.steps
-    # the same step with the bank in the full layout (its zeros written)
-    ms_full_layout = None
-    if not args.main_only:
-        for _ in range(args.warmup):
-            full_layout_step()
-        torch.cuda.synchronize()
-        r0 = time.perf_counter()
-        for _ in range(args.steps):
-            full_layout_step()
-        torch.cuda.synchronize()
-        ms_full_layout = (time.perf_counter() - r0) * 1e3 / args.steps
+    ms_rec = timed(step_rec, args.steps)      # cached transfer function
 
+    E = 2 if key == "pol5" else None
+    # the fluorescence workload (about 10 MB) stays in the caches and its kernels
+    # last a few microseconds each: launch- and latency-bound, no HBM roofline
+    hbm = key != "fluor"
     kernels = {}
     step_bytes = 0
     for name, (cnt, tot) in sorted(kern.items()):
         per = tot / cnt
-        b = kernel_bytes(name, Z, Y, X, sup)
+        b = kernel_bytes(name, Z, Y, X, sup, C, P, E) if hbm else None
         ent = {"launches": cnt, "avg_ms": round(per, 5)}
         if b:
             ent["alg_bytes"] = b
             ent["alg_GBps"] = round(b / (per * 1e-3) / 1e9, 1)
+            ent["hbm_frac"] = round(b / (per * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
             step_bytes += b * cnt // args.steps
         kernels[name] = ent
-    dom_b = kernel_bytes(dom, Z, Y, X, sup) or 0
     dom_ms = dom_rec[1] / dom_rec[0]
-    ach = dom_b / (dom_ms * 1e-3) / 1e9
-    roof = {"kernel": dom, "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": measured_traffic(dom, sup),
-            "alg_bytes": dom_b}
+    if hbm:
+        dom_b = kernel_bytes(dom, Z, Y, X, sup, C, P, E) or 0
+        ach = dom_b / (dom_ms * 1e-3) / 1e9
+        symbols = counter_symbols(sup, Z, X, P, C)
+        roof = {"kernel": dom, "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
+                "traffic": measured_traffic(key, dom, symbols), "alg_bytes": dom_b,
+                "avg_ms_timed_region": round(dom_ms, 5)}
+    else:
+        ach = 0.0
+        roof = {"kernel": dom, "bound": "latency", "avg_ms_timed_region": round(dom_ms, 5),
+                "note": "cache-resident working set, kernels of a few microseconds: launch/latency-bound"}
+    res = {"workload": spec["workload"], "shape_zyx": [Z, Y, X], "channels_x_properties": [C, P],
+           "voxel_um": [o.dz, o.dy, o.dx], "eta": eta,
+           "eta_rule": "1e-3 absolute" if key == "fluor" else "1e-3 * max_nu sigma_max(H(nu))^2",
+           "ms_per_step": ms, "voxels_per_s": V / (ms * 1e-3), "steps": args.steps,
+           "reconstruct_cached_tf": {"ms": ms_rec, "voxels_per_s": V / (ms_rec * 1e-3)},
+           "lateral_support": {k: list(v) if isinstance(v, tuple) else v for k, v in sup.items()},
+           "fft_schedules": tuner, "roofline": roof,
+           # every library kernel of the step: algorithmic bytes per step over the timed
+           # step duration (launch gaps and all)
+           "step_hbm": ({"alg_bytes": step_bytes, "GBps": round(step_bytes / (ms * 1e-3) / 1e9, 1),
+                         "frac": round(step_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)} if hbm else None),
+           "kernels": kernels}
+    print(f"[bench] {key}: {ms:.3f} ms/step, {V / (ms * 1e-3) / 1e9:.2f} G voxels/s; dominant {dom} "
+          f"{dom_ms * 1e3:.1f} us" + (f", {ach:.0f} GB/s" if hbm else ""), file=sys.stderr, flush=True)
+    if parity:
+        d_host = d.cpu().numpy()[0]
+        res["parity"] = (parity_pol5_sampled(o, d_host, f_timed, eta, sup) if key == "pol5"
+                         else parity_full(o, d_host, f_timed, eta))
+        print(f"[bench] {key}: parity {res['parity']['rel_l2']:.2e} ({res['parity']['kind']})",
+              file=sys.stderr, flush=True)
+    del d, ws_tf, ws_rec, fout, bank
+    torch.cuda.empty_cache()
+    return res
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-parity", action="store_true", help="skip the oracle checks of the timed outputs")
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--tune-patches", type=int, default=256)
+    ap.add_argument("--tune-iters", type=int, default=100)
+    ap.add_argument("--cnn-train-patches", type=int, default=16384)
+    ap.add_argument("--cnn-epochs", type=int, default=8)
+    ap.add_argument("--cnn-tune-iters", type=int, default=20)
+    ap.add_argument("--restore-tiles", type=int, default=64)
+    ap.add_argument("--fov-size", type=int, default=2048, help="field of view side (0: skip)")
+    ap.add_argument("--no-multi-aperture", action="store_true")
+    ap.add_argument("--no-aberration", action="store_true")
+    ap.add_argument("--sections", default="pol5,labelfree,fluor",
+                    help="linear workloads to run, the first is the headline")
+    ap.add_argument("--main-only", action="store_true",
+                    help="only the headline linear workload (profiled runs: only its kernels in the trace)")
+    ap.add_argument("--no-fft-tune", action="store_true", help="keep the default FFT schedules")
+    ap.add_argument("--fft-plans", default="", help="import an FFT schedule table instead of tuning")
+    ap.add_argument("--save-fft-plans", default="", help="write the FFT schedule table used")
+    ap.add_argument("--restore-graph", type=int, default=2, choices=(0, 1, 2),
+                    help="graph mode of the CNN-started restoration (multistart uses 1)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a plain 1 GiB device copy (reference for HBM counters)")
+    ap.add_argument("--summarise-trace", default="", help="(no GPU) write the kernel-duration "
+                    "summary of a rocprofv3 --kernel-trace directory to --summary-out")
+    ap.add_argument("--summarise-counters", nargs=2, default=None, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="(no GPU) write the FETCH_SIZE/WRITE_SIZE summary to --summary-out")
+    ap.add_argument("--summary-command", action="append", default=[],
+                    help="command line recorded in the summary header (repeatable)")
+    ap.add_argument("--summary-title", default="", help="workload named in the summary header")
+    ap.add_argument("--summary-out", default="")
+    args = ap.parse_args()
+    if args.summarise_trace or args.summarise_counters:
+        text = (summarise_trace(args.summarise_trace, " ".join(args.summary_command), args.summary_title)
+                if args.summarise_trace else
+                summarise_counters(*args.summarise_counters, args.summary_command, args.summary_title))
+        if args.summary_out:
+            open(args.summary_out, "w").write(text)
+        else:
+            sys.stdout.write(text)
+        return
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus above 1 is not supported"}))
+        sys.exit(2)
+
+    import torch
+
+    from paper_2412_09775_amd import api
+
+    api.load()
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    keys = [k for k in args.sections.split(",") if k]
+    if args.main_only:
+        keys = keys[:1]
+        args.no_multi_aperture = args.no_aberration = args.no_autotune = True
+    results = {}
+    for k in keys:
+        results[k] = linear_section(api, torch, dev, args, k, parity=not args.no_parity)
+    head = results[keys[0]]
+    if args.save_fft_plans:
+        os.makedirs(os.path.dirname(os.path.abspath(args.save_fft_plans)), exist_ok=True)
+        with open(args.save_fft_plans, "w") as fh:
+            fh.write(api.fft_plans_export())
 
     out = {
         "metric": "reconstructed voxels/s (TF synthesis + Tikhonov reconstruction per step)",
-        "value": value,
+        "value": head["voxels_per_s"],
         "unit": "voxels/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms,
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "label-free 3D phase+absorption, 96x512x512, 1 channel x 2 properties "
-                               "(bank kept on its lateral support)",
-                   "shape_zyx": [Z, Y, X], "voxel_um": [o.dz, o.dy, o.dx], "eta_rel": ETA_REL},
-        "lateral_support": {k: list(v) if isinstance(v, tuple) else v for k, v in sup.items()},
-        "reconstruct_cached_tf": {"ms": ms_rec, "voxels_per_s": V / (ms_rec * 1e-3)},
-        "ms_per_step_full_layout_bank": ms_full_layout,
-        "fft_schedules": tuner,
-        "roofline": roof,
-        # every library kernel of the step: algorithmic bytes per step over the
-        # timed step duration (launch gaps and all)
-        "step_hbm": {"alg_bytes": step_bytes, "GBps": round(step_bytes / (ms * 1e-3) / 1e9, 1),
-                     "frac": round(step_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
-        "kernels": kernels,
+        "config": {"workload": head["workload"], "shape_zyx": head["shape_zyx"],
+                   "channels_x_properties": head["channels_x_properties"], "voxel_um": head["voxel_um"],
+                   "eta_rel": ETA_REL},
+        "roofline": head["roofline"],
+        "step_hbm": head["step_hbm"],
+        "parity": head.get("parity"),
+        "reconstruct_cached_tf": head["reconstruct_cached_tf"],
+        "lateral_support": head["lateral_support"],
+        "fft_schedules": head["fft_schedules"],
+        "kernels": head["kernels"],
+        "secondary": {SECTIONS[k]["name"]: results[k] for k in keys[1:]},
     }
 
     if not args.no_multi_aperture:
@@ -459,8 +647,12 @@ def main():
         torch.cuda.synchronize()
         out["copy_calibration_bytes"] = {"read": src.numel() * 4, "write": dst.numel() * 4}
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(o, args.cpu_sample_nz)
+        out["cpu_baseline"] = cpu_baseline(keys[0])
     print(json.dumps(out))
+    bad = [k for k, r in results.items() if r.get("parity") and not r["parity"]["ok"]]
+    if bad:
+        print(f"[bench] parity above tolerance: {bad}", file=sys.stderr, flush=True)
+        sys.exit(1)
 
 
 # Auto-tune workload: 256 patches of 32x128x128 (dz 0.2, dx 0.1 um), lambda0 0.532,
@@ -871,8 +1063,11 @@ def cpu_baseline_autotune(iters_timed=20, iters_full=100):
                       f"{dt:.1f} s, extrapolated to {iters_full} iterations"}
 
 
-def cpu_baseline(o, nz):
-    """FP64 oracle (TF synthesis + reconstruction) on a bounded slab of the workload."""
+def cpu_baseline(key, lateral=256, budget_s=20.0):
+    """The FP64 oracle (TF synthesis + reconstruction, as it stands) timed on the
+    host cores on a bounded sample of the headline workload: its optics and
+    voxel sizes on a lateral crop of the grid (all planes), repeated for about
+    budget_s seconds; voxels per second of that sample."""
     import scipy.fft as sfft
 
     import synth
@@ -880,25 +1075,31 @@ def cpu_baseline(o, nz):
     from oracle import optics as op
     from oracle import tf as tfm
 
+    spec = dict(SECTIONS[key]["optics"])
     cores = len(os.sched_getaffinity(0))
-    oo = op.Optics(model=op.LABELFREE_3D, nz=nz, ny=o.ny, nx=o.nx, dz=o.dz, dy=o.dy, dx=o.dx,
-                   wavelength=o.wavelength, na_ill=o.na_ill, na_det=o.na_det, n_medium=o.n_medium)
-    data = synth.gaussian_noise((1, nz, o.ny, o.nx), 1e-2, 77)
+    ny, nx = min(spec["ny"], lateral), min(spec["nx"], lateral)
+    oo = op.Optics(model=spec["model"], nz=spec["nz"], ny=ny, nx=nx, dz=spec["dz"], dy=spec["dy"],
+                   dx=spec["dx"], wavelength=spec["wavelength"], na_ill=spec["na_ill"], na_det=spec["na_det"],
+                   n_medium=spec["n_medium"], swing=spec["swing"])
+    C = tfm.bank_shape(oo)[0]
+    data = synth.gaussian_noise((C, oo.nz, ny, nx), 1e-2, 77)
     reps, t_tf, t0 = 0, 0.0, time.perf_counter()
     with sfft.set_workers(cores):
         while True:
             a = time.perf_counter()
             bank = tfm.transfer_function(oo)
             t_tf += time.perf_counter() - a
-            eta = ETA_REL * linear.max_singular_value_sq(bank)
+            eta = 1e-3 if key == "fluor" else ETA_REL * linear.max_singular_value_sq(bank)
             linear.reconstruct(bank, data, None, eta)
             reps += 1
-            if time.perf_counter() - t0 > 10.0 or reps >= 20:
+            del bank
+            if time.perf_counter() - t0 > budget_s or reps >= 20:
                 break
     t2 = time.perf_counter()
-    vox = nz * o.ny * o.nx * reps
+    vox = oo.nz * ny * nx * reps
     return {"value": vox / (t2 - t0), "unit": "voxels/s", "cores": cores, "kind": "oracle",
-            "sample": f"{reps} x ({nz}x{o.ny}x{o.nx} volume: TF synthesis + reconstruction, FP64)",
+            "sample": f"{reps} x ({oo.nz}x{ny}x{nx} crop of the workload's grid, same optics and voxels: "
+                      f"TF synthesis + reconstruction, FP64)",
             "seconds": round(t2 - t0, 2), "tf_seconds": round(t_tf, 2)}
 
 
