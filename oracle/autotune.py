@@ -166,6 +166,22 @@ def loss_and_gradient(o: op.Optics, d: np.ndarray, eta: float, nu_c: float):
     HY = np.einsum("ncp,np->nc", Hn, Yv)
     GH = r[:, :, None] * np.conj(Yv)[:, None, :] - HY[:, :, None] * np.conj(Fn)[:, None, :]
     GH = np.moveaxis(GH, 0, 2).reshape(Z, 2, Y, X)
+    return L, _pair_gradient_to_theta(o, zs, GH, a, b)
+
+
+def _pair_gradient_to_theta(o: op.Optics, zs, GH: np.ndarray, a: np.ndarray, b: np.ndarray) -> np.ndarray:
+    """dL/dtheta from the gradient GH = dL/dH_z* (Z, 2, Y, X) of the per-plane 2D
+    label-free pair H_z = [fft2(2 Re c_z), fft2(-2 Im c_z)] at the planes zs,
+    c_z = (N / I_bg) b_z conj(a_z), a_z, b_z the inverse 2D transforms of the
+    direct and scattered arms (Table 1's label-free row), by reverse mode
+    through c, the arms and the pupils."""
+    Y, X = o.ny, o.nx
+    N = Y * X
+    S, P, dP_dna, dS_dzen, dS_daz = pupil_derivatives(o)
+    g = op.greens_spectrum(o)
+    kz = op.axial_wavenumber(o)
+    ibg = float(np.sum(S * P * P))
+    s = N / ibg
     # back through H = fft2(2 Re c), fft2(-2 Im c): Gamma = Re(N ifft2 G_ph) + i Re(N ifft2 G_abs)
     gam = N * sfft.ifft2(GH, axes=(-2, -1))
     Gam = gam[:, 0].real + 1j * gam[:, 1].real              # (Z, Y, X)
@@ -186,7 +202,98 @@ def loss_and_gradient(o: op.Optics, d: np.ndarray, eta: float, nu_c: float):
     # s = N / I_bg, I_bg = sum S P^2
     dibg = np.array([0.0, np.sum(2.0 * S * P * dP_dna), np.sum(dS_dzen * P * P), np.sum(dS_daz * P * P)])
     grad += ds_term * (-s / ibg) * dibg
-    return L, grad
+    return grad
+
+
+# --- gradient of a loss of the 3D reconstruction (Ext. Data Fig. 3, backpropagation
+# through the Tikhonov inverse into the transfer-function synthesis)
+
+def recon_objective(o: op.Optics, d: np.ndarray, eta: float, w: np.ndarray, b=None) -> float:
+    """L = sum_r w(r) f(r), f = the Tikhonov reconstruction of d with the bank of o
+    (a loss linear in f; any loss enters the reverse mode only through dL/df = w)."""
+    f = linear.reconstruct(tfm.transfer_function(o), d, b, eta)
+    return float(np.sum(np.asarray(w, dtype=np.float64) * f))
+
+
+def recon_fd_gradient(o: op.Optics, d, eta, w, steps, b=None, which=(0, 1, 2, 3)) -> np.ndarray:
+    """dL/dtheta of recon_objective by central differences with one Richardson step."""
+    th = theta_of(o)
+    g = np.zeros(4)
+    for j in which:
+        def cd(h):
+            tp, tm = th.copy(), th.copy()
+            tp[j] += h
+            tm[j] -= h
+            return (recon_objective(with_theta(o, tp), d, eta, w, b)
+                    - recon_objective(with_theta(o, tm), d, eta, w, b)) / (2 * h)
+        h = steps[j]
+        g[j] = (4.0 * cd(h / 2) - cd(h)) / 3.0
+    return g
+
+
+def recon_gradient(o: op.Optics, d: np.ndarray, eta: float, w: np.ndarray, b=None):
+    """Reverse mode for a loss L of the 3D reconstruction f given w = dL/df
+    (P, Z, Y, X): returns (dL/dtheta (4,), dL/dd (C, Z, Y, X)).  Label-free 3D and
+    the 5 x 4 polarisation bank (whose entries are Re(kappa) H_phase +
+    Im(kappa) H_abs of the label-free pair).
+
+    Per 3D frequency, F = M^-1 H^H (D - N b delta), M = H^H H + eta I; with
+    dL/dF* = FFT3(w) / (2 N) (f = Re IFFT3 F), Y = M^-1 dL/dF*, R = D - N b delta - H F:
+    dL/dH* = R Y^H - H Y F^H and dL/dd = Re IFFT3(2 N H Y).  The 3D pair is the
+    axial DFT of the per-plane 2D pair, H(kz) = sum_z e^{-i 2 pi kz z / Z} H_z, so
+    dL/dH_z* = sum_kz e^{+i 2 pi kz z / Z} dL/dH(kz)* (the unnormalised inverse
+    DFT), after which the chain is the per-plane one of the thin model."""
+    if o.model not in (op.LABELFREE_3D, op.POL5_3D):
+        raise ValueError("label-free 3D or polarisation models only")
+    if any(z != 0 for z in o.zernike):
+        raise ValueError("unaberrated optics only (aberrated: recon_fd_gradient)")
+    Z, Y, X = o.nz, o.ny, o.nx
+    N = Z * Y * X
+    zs = op.z_planes_3d(o)
+    S = op.illumination_pupil(o)
+    P = op.detection_pupil(o)
+    g = op.greens_spectrum(o)
+    kzz = op.axial_wavenumber(o)
+    ibg = float(np.sum(S * P * P))
+    a = np.empty((Z, Y, X), np.complex128)
+    bb = np.empty((Z, Y, X), np.complex128)
+    for k, z in enumerate(zs):
+        prop = np.exp(2j * np.pi * kzz * (z - o.defocus))
+        a[k] = sfft.ifft2(S * P * prop)
+        bb[k] = sfft.ifft2(P * g * prop)
+    c = (Y * X / ibg) * bb * np.conj(a)
+    hp, ha = sfft.fftn(2.0 * c.real), sfft.fftn(-2.0 * c.imag)
+    if o.model == op.POL5_3D:
+        kap = tfm.pol5_coupling(o.swing)
+        bank = kap.real[:, :, None, None, None] * hp + kap.imag[:, :, None, None, None] * ha
+    else:
+        kap = None
+        bank = np.stack([hp, ha])[None]
+    C, Pn = bank.shape[:2]
+    D = sfft.fftn(np.asarray(d, dtype=np.float64), axes=(-3, -2, -1))
+    if b is not None:
+        D[:, 0, 0, 0] -= N * np.asarray(b, dtype=np.float64)
+    Gw = sfft.fftn(np.asarray(w, dtype=np.float64), axes=(-3, -2, -1)) / (2.0 * N)
+    Hn = np.moveaxis(bank.reshape(C, Pn, -1), 2, 0)            # (n, C, P)
+    Dn = np.moveaxis(D.reshape(C, -1), 1, 0)                    # (n, C)
+    Gn = np.moveaxis(Gw.reshape(Pn, -1), 1, 0)                  # (n, P)
+    Hh = np.conj(np.swapaxes(Hn, 1, 2))
+    M = Hh @ Hn + eta * np.eye(Pn)[None]
+    Fn = np.linalg.solve(M, np.einsum("npc,nc->np", Hh, Dn)[..., None])[..., 0]
+    Yv = np.linalg.solve(M, Gn[..., None])[..., 0]
+    r = Dn - np.einsum("ncp,np->nc", Hn, Fn)
+    HY = np.einsum("ncp,np->nc", Hn, Yv)
+    GH = r[:, :, None] * np.conj(Yv)[:, None, :] - HY[:, :, None] * np.conj(Fn)[:, None, :]   # (n, C, P)
+    if kap is None:
+        Gpair = GH[:, 0, :]                                      # (n, 2)
+    else:
+        # dH_cp = Re(kappa_cp) dH_phase + Im(kappa_cp) dH_abs with real coefficients
+        Gpair = np.stack([np.einsum("cp,ncp->n", kap.real, GH), np.einsum("cp,ncp->n", kap.imag, GH)], 1)
+    G3 = np.moveaxis(Gpair, 0, 1).reshape(2, Z, Y, X)
+    Gz = Z * sfft.ifft(G3, axis=1)                               # unnormalised inverse DFT along z
+    grad = _pair_gradient_to_theta(o, zs, np.moveaxis(Gz, 0, 1), a, bb)
+    dd = sfft.ifftn((2.0 * N) * np.moveaxis(HY, 0, 1).reshape(C, Z, Y, X), axes=(-3, -2, -1)).real
+    return grad, dd
 
 
 # --- optimiser

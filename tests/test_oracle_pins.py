@@ -534,3 +534,50 @@ def test_sector_point_response_is_abbe_source_sum():
         got = tfm.labelfree_point_response(o, Sc)
         ref = abbe_point_response(o, Sc)
         assert np.allclose(got, ref, atol=1e-12 * np.abs(ref).max())
+
+
+# ---------------------------------------------------------------- gradient of the 3D reconstruction
+
+def _recon_case(model, seed=0, **kw):
+    import synth
+    base = dict(model=model, nz=6, ny=16, nx=16, dz=0.25, dy=0.13, dx=0.13, wavelength=0.532,
+                na_ill=0.4, na_det=0.9, n_medium=1.33, defocus=0.12, tilt_zenith=0.15, tilt_azimuth=0.4,
+                edge_width=0.5, swing=0.1)
+    base.update(kw)
+    o = op.Optics(**base)
+    C, P, _ = tfm.bank_shape(o)
+    rng = np.random.default_rng(seed)
+    d = rng.normal(size=(C, o.nz, o.ny, o.nx))
+    w = rng.normal(size=(P, o.nz, o.ny, o.nx))
+    eta = 1e-2 * linear.max_singular_value_sq(tfm.transfer_function(o))
+    return o, d, w, eta
+
+
+@pytest.mark.parametrize("model", [op.LABELFREE_3D, op.POL5_3D])
+def test_recon_gradient_matches_finite_differences(model):
+    """Reverse mode through the Tikhonov inverse and the 3D synthesis (Ext. Data
+    Fig. 3) against central differences of the plain definition L = <w, R_eta d>."""
+    o, d, w, eta = _recon_case(model)
+    grad, _ = at.recon_gradient(o, d, eta, w)
+    fd = at.recon_fd_gradient(o, d, eta, w, steps=(1e-5, 1e-5, 1e-5, 1e-5))
+    scale = np.max(np.abs(fd))
+    assert np.max(np.abs(grad - fd)) < 1e-6 * scale, (grad, fd)
+
+
+def test_recon_gradient_with_a_background_and_odd_depth():
+    o, d, w, eta = _recon_case(op.LABELFREE_3D, seed=3, nz=5, defocus=-0.2, tilt_zenith=0.05)
+    b = np.array([0.3])
+    grad, _ = at.recon_gradient(o, d, eta, w, b=b)
+    fd = at.recon_fd_gradient(o, d, eta, w, steps=(1e-5,) * 4, b=b)
+    assert np.max(np.abs(grad - fd)) < 1e-6 * np.max(np.abs(fd))
+
+
+@pytest.mark.parametrize("model", [op.LABELFREE_3D, op.POL5_3D])
+def test_recon_data_gradient_is_the_transpose_of_the_reconstruction(model):
+    """dL/dd = R_eta^T w: <dL/dd, e> = <w, R_eta e> for any e (dot-product test)."""
+    o, d, w, eta = _recon_case(model, seed=5)
+    _, dd = at.recon_gradient(o, d, eta, w)
+    e = np.random.default_rng(9).normal(size=d.shape)
+    lhs = float(np.sum(dd * e))
+    rhs = float(np.sum(w * linear.reconstruct(tfm.transfer_function(o), e, None, eta)))
+    assert abs(lhs - rhs) < 1e-10 * abs(rhs)
