@@ -72,7 +72,9 @@ enum {
   WO_EUNSUPPORTED = -2,  /* size or mode the kernels do not implement */
   WO_ENOMEM = -3,        /* workspace smaller than wo_workspace_size() */
   WO_EHIP = -4,          /* the HIP runtime reported an error */
-  WO_EALIAS = -5         /* transfer-function support exceeds the sampled band */
+  WO_EALIAS = -5,        /* transfer-function support exceeds the sampled band */
+  WO_DIVERGED = -6       /* per patch (wo_autotune status_out): no start ended with a
+                            finite loss and finite parameters */
 };
 
 enum {
@@ -198,10 +200,13 @@ int wo_transfer_function_band(const wo_optics* o, int32_t n, void* tf_out, void*
 /* wo_forward (op WO_OP_FORWARD: in = f, out = d, eta ignored), wo_reconstruct
  * (WO_OP_RECONSTRUCT: in = d, out = f) or wo_adjoint (WO_OP_ADJOINT: in = r,
  * out = g, b ignored) with the bank in the band layout of
- * wo_transfer_function_band (POL5_3D: the reduced form, whose entries the
- * fused Z pass forms per frequency from the pair and the coupling of each
- * patch's swing); results bit for bit those of the full-layout call.  3D
- * models only (thin: WO_EUNSUPPORTED); workspace as for those calls. */
+ * wo_transfer_function_band; results bit for bit those of the full-layout
+ * call.  POL5_3D takes the reduced form: the forward model and the adjoint
+ * form the entries per frequency from the pair and each patch's coupling (bit
+ * for bit as above); the reconstruction forms H^H H and H^H x from the pair and
+ * constants of the coupling without the entries (the same solve up to FP32
+ * rounding order).  3D models only (thin: WO_EUNSUPPORTED); workspace as for
+ * those calls. */
 int wo_linear_band(int32_t op, const wo_optics* o, int32_t n, const void* tf, const float* in,
                    const float* b, double eta, float* out, void* ws, size_t ws_bytes, void* stream);
 
@@ -219,6 +224,33 @@ int wo_pol5_coupling(double swing, float* kappa_out);
 /* Adjoint g_p = IFFT(sum_c conj(H_cp) R_c): r [n][C][vol] -> g_out [n][P][vol]. */
 int wo_adjoint(const wo_optics* o, int32_t n, const void* tf, const float* r, float* g_out,
                void* ws, size_t ws_bytes, void* stream);
+
+/* Gradient of a scalar loss of the Tikhonov reconstruction with respect to
+ * the optics and the data (Ext. Data Fig. 3: backpropagation through the
+ * Tikhonov inverse into the transfer-function synthesis; Results,
+ * "Physics-guided ML auto-tunes multi-contrast blind deconvolution").  Given
+ * dL/df of the reconstruction f = wo_reconstruct(transfer function of o, d, b,
+ * eta), returns dL/dtheta for theta = (defocus, na_det, tilt_zenith,
+ * tilt_azimuth) of each patch and dL/dd.  The transfer function is recomputed
+ * from o (not stored), the same bank wo_transfer_function writes.  Per 3D
+ * frequency, with x = D - N b delta, M = H^H H + eta I, F = M^-1 H^H x:
+ * dL/dF* = FFT3(dL/df) / (2N), Y = M^-1 dL/dF*, dL/dH* = (x - H F) Y^H - H Y F^H,
+ * dL/dd = Re IFFT3(2N H Y); dL/dH* then goes back through the 3D transform of
+ * the per-plane label-free pair (whose adjoint along z is the unnormalised
+ * inverse DFT), the correlation of the two arms and the pupils (analytic
+ * derivatives of the soft edge; hard edges give no NA or tilt gradient).
+ * Aberrated optics are accepted (dL/dNA includes the aberration's NA
+ * dependence).  Models LABELFREE_3D and POL5_3D (whose 5 x 4 bank is the
+ * coupling's mix of the pair); others WO_EUNSUPPORTED.
+ * d: device [n][C][vol]; b: device [n][C] or NULL; eta > 0; dL_df: device
+ * [n][P][vol]; dL_dtheta_out: host [n][4] or NULL; dL_dd_out: device
+ * [n][C][vol] or NULL (not both NULL).  Workspace of
+ * wo_reconstruct_grad_workspace_size bytes (0: unsupported model).
+ * Synchronises `stream` when dL_dtheta_out is not NULL. */
+size_t wo_reconstruct_grad_workspace_size(const wo_optics* o, int32_t n);
+int wo_reconstruct_grad(const wo_optics* o, int32_t n, const float* d, const float* b, double eta,
+                        const float* dL_df, double* dL_dtheta_out, float* dL_dd_out, void* ws,
+                        size_t ws_bytes, void* stream);
 
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid allocation):
@@ -312,13 +344,20 @@ typedef struct wo_autotune_opts {
                               bit 4 + j tunes zernike[j] (Noll 5 + j), starting from
                               each patch's optics (also for every multistart start) */
   double zernike_bound;    /* box [-bound, bound] waves for them (<= 0: 1 wave) */
+  int32_t* status_out;     /* host [n] per-patch status, or NULL: WO_OK, or WO_DIVERGED
+                              when no start of the patch ended with a finite loss and
+                              finite parameters (the patch's optics are then left as
+                              they were passed and its loss_out is NaN; the call itself
+                              still returns WO_OK) */
 } wo_autotune_opts;
 
 /* Adam (beta 0.9, 0.999, eps 1e-8) on theta for opts->iters iterations, every
  * patch and start in one batched launch sequence; theta is clipped to the box
  * after each step.  On return o[i] holds the best start's theta (and tuned
- * aberration coefficients) and
- * loss_out[i] (host, may be NULL) its loss at that theta.  d: device, packed
+ * aberration coefficients): the lowest final loss among the starts that ended
+ * finite; loss_out[i] (host, may be NULL) its loss at that theta.  A patch
+ * none of whose starts ended finite (for instance non-finite data) is
+ * reported in opts->status_out and does not fail the batch.  d: device, packed
  * stacks; eta: host [n].  Not reentrant across host threads (calls
  * serialise on a library lock).  Synchronises `stream` before returning. */
 int wo_autotune(wo_optics* o, int32_t n, const float* d, const double* eta,

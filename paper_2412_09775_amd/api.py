@@ -30,6 +30,8 @@ OP_FORWARD = 1
 OP_RECONSTRUCT = 2
 OP_ADJOINT = 3
 
+DIVERGED = -6   # WO_DIVERGED
+
 SYMBOLS = ("wo_bank_shape", "wo_workspace_size", "wo_transfer_function", "wo_forward",
            "wo_reconstruct", "wo_adjoint", "wo_strerror", "wo_version", "wo_timing_enable",
            "wo_timing_report", "wo_tune_workspace_size", "wo_midband_loss_grad", "wo_autotune",
@@ -40,7 +42,8 @@ SYMBOLS = ("wo_bank_shape", "wo_workspace_size", "wo_transfer_function", "wo_for
            "wo_fft_plans_export", "wo_fft_plans_import", "wo_fft_plans_clear", "wo_fft_candidates",
            "wo_tile_grid", "wo_stitch_tiles", "wo_timing_select", "wo_midband_loss_grad_aberration",
            "wo_lateral_support", "wo_transfer_function_band",
-           "wo_linear_band", "wo_reconstruct_noalloc", "wo_pol5_coupling")
+           "wo_linear_band", "wo_reconstruct_noalloc", "wo_pol5_coupling",
+           "wo_reconstruct_grad_workspace_size", "wo_reconstruct_grad")
 
 _FIELDS = ("model", "nz", "ny", "nx", "dz", "dy", "dx", "wavelength", "na_ill", "na_det",
            "n_medium", "defocus", "tilt_zenith", "tilt_azimuth", "edge_width", "swing")
@@ -85,7 +88,8 @@ class WoAutotuneOpts(ctypes.Structure):
                 ("theta0", ctypes.POINTER(ctypes.c_double)), ("nu_c", ctypes.POINTER(ctypes.c_double)),
                 ("all_theta_out", ctypes.POINTER(ctypes.c_double)),
                 ("all_loss_out", ctypes.POINTER(ctypes.c_double)), ("branches", ctypes.c_int32),
-                ("lr_zernike", ctypes.c_double), ("zernike_bound", ctypes.c_double)]
+                ("lr_zernike", ctypes.c_double), ("zernike_bound", ctypes.c_double),
+                ("status_out", ctypes.POINTER(ctypes.c_int32))]
 
 
 class WoSupport(ctypes.Structure):
@@ -126,6 +130,10 @@ def load(path: str = LIB_PATH):
     lib.wo_linear_band.argtypes = [i32, op, i32, vp, vp, vp, ctypes.c_double, vp, vp, sz, vp]
     lib.wo_reconstruct_noalloc.argtypes = [op, i32, vp, vp, vp, ctypes.c_double, vp, vp]
     lib.wo_pol5_coupling.argtypes = [ctypes.c_double, ctypes.POINTER(ctypes.c_float)]
+    lib.wo_reconstruct_grad_workspace_size.argtypes = [op, i32]
+    lib.wo_reconstruct_grad_workspace_size.restype = sz
+    lib.wo_reconstruct_grad.argtypes = [op, i32, vp, vp, ctypes.c_double, vp,
+                                        ctypes.POINTER(ctypes.c_double), vp, vp, sz, vp]
     lib.wo_strerror.argtypes = [ctypes.c_int]
     lib.wo_strerror.restype = ctypes.c_char_p
     lib.wo_version.restype = ctypes.c_int
@@ -324,6 +332,29 @@ def reconstruct_noalloc(optics, tf, d, eta, b=None, out=None, stream=None):
     return out
 
 
+def reconstruct_grad(optics, d, eta, dL_df, b=None, want_theta=True, want_data=True, ws=None,
+                     stream=None):
+    """Gradient of a loss of the reconstruction (``wo_reconstruct_grad``): returns
+    (dL/dtheta numpy (n, 4) or None, dL/dd tensor (n, C, *vol) or None)."""
+    import numpy as np
+    import torch
+    lib = load()
+    arr = optics_array(optics)
+    n = len(arr)
+    need = int(lib.wo_reconstruct_grad_workspace_size(arr, n))
+    if need == 0:
+        raise WoError(-2, "wo_reconstruct_grad_workspace_size")
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(need, dtype=torch.uint8, device=d.device)
+    gth = np.zeros((n, 4)) if want_theta else None
+    gd = torch.empty_like(d) if want_data else None
+    _check(lib.wo_reconstruct_grad(arr, n, _ptr(d.contiguous()), _ptr(b), ctypes.c_double(eta),
+                                   _ptr(dL_df.contiguous()),
+                                   gth.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if want_theta else None,
+                                   _ptr(gd), _ptr(ws), ws.numel(), _stream(stream)), "wo_reconstruct_grad")
+    return gth, gd
+
+
 def band_dims(optics):
     """Tensor shape of one call's bank in the band layout: (n, C, P, Z, band rows, columns);
     the polarisation model's reduced form is the label-free pair, (n, 1, 2, ...)."""
@@ -455,7 +486,7 @@ def midband_loss_grad(optics, d, eta, nu_c=None, ws=None, stream=None, aberratio
 
 
 def _tune_call(fn, name, optics, d, eta, iters, lr, lo, hi, mask, multistart, theta0, nu_c, use_graph,
-               branches, ws, stream, extra, lr_zernike=0.0, zernike_bound=0.0):
+               branches, ws, stream, extra, lr_zernike=0.0, zernike_bound=0.0, status=None):
     import copy
     import numpy as np
     import torch
@@ -486,6 +517,10 @@ def _tune_call(fn, name, optics, d, eta, iters, lr, lo, hi, mask, multistart, th
     all_loss = np.zeros((n, M))
     opts.all_theta_out = all_theta.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
     opts.all_loss_out = all_loss.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    if status is not None:
+        if status.dtype != np.int32 or status.size < n or not status.flags["C_CONTIGUOUS"]:
+            raise ValueError("status must be a contiguous int32 array of n entries")
+        opts.status_out = status.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
     eta_a, eta_p = _dbl(np.broadcast_to(eta, (n,)))
     loss = np.zeros(n)
     _check(fn(arr, n, _ptr(d), eta_p, ctypes.byref(opts),
@@ -511,18 +546,20 @@ def _tune_call(fn, name, optics, d, eta, iters, lr, lo, hi, mask, multistart, th
 
 def autotune(optics, d, eta, iters=100, lr=PAPER_LR, lo=(-1e300,) * 4, hi=(1e300,) * 4,
              mask=0b0111, multistart=1, theta0=None, nu_c=None, use_graph=False, branches=0, ws=None,
-             stream=None, lr_zernike=0.0, zernike_bound=0.0):
+             stream=None, lr_zernike=0.0, zernike_bound=0.0, status=None):
     """Adam auto-tune of theta for every patch; returns (optics list, loss, all_theta, all_loss).
     `d` as in pack_stacks; use_graph 0/False, 1/True (one iteration replayed) or 2 (one launch).
-    mask bits 4..10 also tune the Zernike coefficients (rate lr_zernike, box +-zernike_bound)."""
+    mask bits 4..10 also tune the Zernike coefficients (rate lr_zernike, box +-zernike_bound).
+    status: optional int32 numpy array (n,) that receives each patch's status (0 or
+    WO_DIVERGED = -6)."""
     return _tune_call(load().wo_autotune, "wo_autotune", optics, d, eta, iters, lr, lo, hi, mask,
                       multistart, theta0, nu_c, use_graph, branches, ws, stream, (),
-                      lr_zernike, zernike_bound)
+                      lr_zernike, zernike_bound, status)
 
 
 def restore_tiles(optics, d, eta, iters=20, lr=PAPER_LR, lo=(-1e300,) * 4, hi=(1e300,) * 4,
                   mask=0b0111, multistart=1, theta0=None, nu_c=None, use_graph=2, branches=0,
-                  f_out=None, ws=None, stream=None, lr_zernike=0.0, zernike_bound=0.0):
+                  f_out=None, ws=None, stream=None, lr_zernike=0.0, zernike_bound=0.0, status=None):
     """Auto-tune then thin reconstruction of uneven tiles.  Returns (optics list, loss,
     all_theta, all_loss, f) with f a list of [2, Y_i, X_i] views into one packed buffer."""
     import torch
@@ -534,7 +571,7 @@ def restore_tiles(optics, d, eta, iters=20, lr=PAPER_LR, lo=(-1e300,) * 4, hi=(1
     lib = load()
     res = _tune_call(lib.wo_restore_tiles, "wo_restore_tiles", optics, d, eta, iters, lr, lo, hi, mask,
                      multistart, theta0, nu_c, use_graph, branches, ws, stream, (_ptr(f_out),),
-                     lr_zernike, zernike_bound)
+                     lr_zernike, zernike_bound, status)
     views, off = [], 0
     for o, sz in zip(optics, sizes):
         views.append(f_out[off:off + sz].view(2, int(_get(o, "ny")), int(_get(o, "nx"))))
@@ -581,7 +618,35 @@ def _autograd():
             (grad,) = ctx.saved_tensors
             return gout[:, None] * grad, None, None, None, None
 
-    return LinearForward, MidbandLoss
+    class Reconstruct(torch.autograd.Function):
+        """Tikhonov reconstruction f(d, theta) of a 3D model with theta (n, 4)
+        (float64, host) the optics' (defocus, na_det, tilt_zenith, tilt_azimuth);
+        forward: wo_transfer_function + wo_reconstruct at theta; backward:
+        wo_reconstruct_grad (dL/dd and dL/dtheta, the bank recomputed)."""
+
+        @staticmethod
+        def forward(ctx, d, theta, optics, eta, b):
+            import copy
+            opts = []
+            for i, o in enumerate(optics):
+                oo = copy.copy(o)
+                for j, f in enumerate(PARAMS):
+                    setattr(oo, f, float(theta[i, j]))
+                opts.append(oo)
+            ctx.opts, ctx.eta, ctx.b = opts, eta, b
+            ctx.save_for_backward(d)
+            tf = transfer_function(opts, device=d.device)
+            return reconstruct(opts, tf, d, eta, b=b)
+
+        @staticmethod
+        def backward(ctx, g):
+            (d,) = ctx.saved_tensors
+            gth, gd = reconstruct_grad(ctx.opts, d, ctx.eta, g.contiguous(), b=ctx.b,
+                                       want_theta=ctx.needs_input_grad[1],
+                                       want_data=ctx.needs_input_grad[0])
+            return (gd, None if gth is None else torch.from_numpy(gth), None, None, None)
+
+    return LinearForward, MidbandLoss, Reconstruct
 
 
 def linear_forward_fn(f, optics, tf, b=None):
@@ -592,6 +657,12 @@ def linear_forward_fn(f, optics, tf, b=None):
 def midband_loss_fn(theta, optics, d, eta, nu_c=None):
     """Differentiable mid-band loss in theta (backward = hand-written TF gradient)."""
     return _autograd()[1].apply(theta, optics, d, eta, nu_c)
+
+
+def reconstruct_fn(d, theta, optics, eta, b=None):
+    """Differentiable 3D reconstruction in the data d and theta (n, 4) (backward =
+    wo_reconstruct_grad)."""
+    return _autograd()[2].apply(d, theta, optics, eta, b)
 
 
 # ---------------------------------------------------------------- CNN and training data

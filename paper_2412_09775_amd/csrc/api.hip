@@ -262,6 +262,23 @@ Coupling coupling_of(double swing) {
   for (int i = 0; i < 5; ++i)
     for (int p = 0; p < 4; ++p)
       for (int r = 0; r < 2; ++r) c.k[i][p][r] = (float)k[i][p][r];
+  // Gram constants: with H_cp = Kr_cp u + Ki_cp v, (H^H H)_pq = A_pq |u|^2 +
+  // B_pq |v|^2 + G_pq conj(u) v + G_qp u conj(v), G = Kr^T Ki
+  for (int p = 0; p < 4; ++p)
+    for (int q = 0; q <= p; ++q) {
+      double a = 0, b = 0, gpq = 0, gqp = 0;
+      for (int i = 0; i < 5; ++i) {
+        a += k[i][p][0] * k[i][q][0];
+        b += k[i][p][1] * k[i][q][1];
+        gpq += k[i][p][0] * k[i][q][1];
+        gqp += k[i][q][0] * k[i][p][1];
+      }
+      const int e = p * (p + 1) / 2 + q;
+      c.a[e] = (float)a;
+      c.b[e] = (float)b;
+      c.s[e] = (float)(gpq + gqp);
+      c.d[e] = (float)(gpq - gqp);
+    }
   return c;
 }
 
@@ -1040,20 +1057,29 @@ int run_tune(wo_optics* o, int32_t n, const float* d, const double* eta,
     WO_TRY(hipMemcpyAsync(ho.data(), w + g.base + L.off_opt, L.nv * sizeof(DevOptics),
                           hipMemcpyDeviceToHost, hs));
     WO_TRY(hipStreamSynchronize(hs));
+    auto finite = [&](int v) {
+      bool ok = isfinite(h[v].loss) && isfinite(ho[v].defocus) && isfinite(ho[v].na_det) &&
+                isfinite(ho[v].tilt_zenith) && isfinite(ho[v].tilt_azimuth);
+      for (int k = 0; k < 7; ++k) ok = ok && isfinite(ho[v].zern[k]);
+      return ok;
+    };
     for (int j = 0; j < L.np; ++j) {
       const int i = g.idx[j];
-      int best = j * starts;
-      for (int s2 = 1; s2 < starts; ++s2) {
+      int best = -1;   // the lowest final loss among the starts that ended finite
+      for (int s2 = 0; s2 < starts; ++s2) {
         const int v = j * starts + s2;
-        if (h[v].loss < h[best].loss) best = v;
+        if (finite(v) && (best < 0 || h[v].loss < h[best].loss)) best = v;
       }
-      o[i].defocus = ho[best].defocus;
-      o[i].na_det = ho[best].na_det;
-      o[i].tilt_zenith = ho[best].tilt_zenith;
-      o[i].tilt_azimuth = ho[best].tilt_azimuth;
-      if ((opts->tune_mask >> 4) & 0x7f)
-        for (int k = 0; k < 7; ++k) o[i].zernike[k] = ho[best].zern[k];
-      if (loss_out) loss_out[i] = h[best].loss;
+      if (opts->status_out) opts->status_out[i] = best < 0 ? WO_DIVERGED : WO_OK;
+      if (best >= 0) {
+        o[i].defocus = ho[best].defocus;
+        o[i].na_det = ho[best].na_det;
+        o[i].tilt_zenith = ho[best].tilt_zenith;
+        o[i].tilt_azimuth = ho[best].tilt_azimuth;
+        if ((opts->tune_mask >> 4) & 0x7f)
+          for (int k = 0; k < 7; ++k) o[i].zernike[k] = ho[best].zern[k];
+      }
+      if (loss_out) loss_out[i] = best >= 0 ? h[best].loss : NAN;
       if (opts->all_theta_out)
         for (int s2 = 0; s2 < starts; ++s2) {
           const int v = j * starts + s2;
@@ -1073,7 +1099,7 @@ int run_tune(wo_optics* o, int32_t n, const float* d, const double* eta,
 
 extern "C" {
 
-int wo_version(void) { return 100; }
+int wo_version(void) { return 200; }
 
 int wo_timing_enable(int on) {
   std::lock_guard<std::mutex> lk(wo::g_tmu);
@@ -1134,6 +1160,7 @@ const char* wo_strerror(int status) {
              "wo_reconstruct_noalloc)";
     case WO_EHIP: return "HIP runtime error";
     case WO_EALIAS: return "transfer-function support exceeds the sampled band";
+    case WO_DIVERGED: return "no start of the patch ended with a finite loss and parameters";
     default: return "unknown status";
   }
 }
@@ -1401,6 +1428,149 @@ int wo_adjoint(const wo_optics* o, int32_t n, const void* tf, const float* r, fl
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------- gradient of a loss of the 3D reconstruction
+
+namespace {
+
+// Columns the gradient of the 3D reconstruction keeps of both fields: the
+// detection pupil's lateral support (the source's lies within it), which holds
+// the pupils' derivatives too (the soft edge is inside the bound); transforms
+// on the grid's own lengths.
+LatSupport grad3_support(const wo_optics* o, int32_t n) {
+  const Sampling sm = sampling_of(o);
+  LatSupport ls = full_support(sm);
+  const LatSupport lat = lateral_support(o, n);
+  ls.xc = ls.xa = lat.xc;
+  ls.kp = ls.kpa = lat.kp;
+  return ls;
+}
+
+struct Grad3Layout {
+  size_t opt, st, pp, lp, dp, gp, ip, ab, bank, D, G, cpl, total;
+};
+
+Grad3Layout grad3_layout(const wo_optics* o, int32_t n, const Shape& s, const LatSupport& sup) {
+  const Sampling sm = sampling_of(o);
+  const long plane = s.Y * s.Xh;
+  Grad3Layout L;
+  size_t b = 0;
+  auto take = [&](size_t bytes) { size_t o0 = b; b += align_up(bytes); return o0; };
+  L.opt = take((size_t)n * sizeof(DevOptics));
+  L.st = take((size_t)n * sizeof(TuneState));
+  L.pp = take((size_t)n * ((s.X + tf_tile_width(sm) - 1) / tf_tile_width(sm)) * sizeof(double));
+  L.lp = take((size_t)n * loss_blocks(sm) * sizeof(double));
+  L.dp = take((size_t)n * bwd_wg_per_patch(sm) * sizeof(double));
+  L.gp = take((size_t)n * s.Z * grad_tiles(sm) * kGradAll * sizeof(double));
+  L.ip = take((size_t)n * grad_tiles(sm) * 4 * sizeof(double));
+  L.ab = take((size_t)n * 2 * s.Z * s.Y * sup.xc * sizeof(float2));
+  L.bank = take((size_t)n * s.Z * 2 * plane * sizeof(float2));
+  L.D = take((size_t)n * s.C * s.Z * plane * sizeof(float2));
+  L.G = take((size_t)n * s.P * s.Z * plane * sizeof(float2));
+  L.cpl = take((size_t)n * sizeof(Coupling));
+  L.total = b;
+  return L;
+}
+
+bool grad3_model(const wo_optics* o) {
+  return o->model == WO_MODEL_LABELFREE_3D || o->model == WO_MODEL_POL5_3D;
+}
+
+}  // namespace
+
+extern "C" size_t wo_reconstruct_grad_workspace_size(const wo_optics* o, int32_t n) {
+  Shape s;
+  if (!o || n < 1 || !bank_shape(o, &s) || !grad3_model(o)) return 0;
+  return grad3_layout(o, n, s, grad3_support(o, n)).total;
+}
+
+extern "C" int wo_reconstruct_grad(const wo_optics* o, int32_t n, const float* d, const float* b,
+                                   double eta, const float* dL_df, double* dL_dtheta_out, float* dL_dd_out,
+                                   void* ws, size_t ws_bytes, void* stream) {
+  int st = validate(o, n);
+  if (st) return st;
+  if (!grad3_model(o)) return WO_EUNSUPPORTED;
+  if (!d || !dL_df || !ws || (!dL_dtheta_out && !dL_dd_out)) return WO_EINVAL;
+  if (!(eta > 0.0) || !isfinite(eta)) return WO_EINVAL;
+  Shape s;
+  bank_shape(o, &s);
+  const LatSupport sup = grad3_support(o, n);
+  const Grad3Layout L = grad3_layout(o, n, s, sup);
+  if (ws_bytes < L.total) return WO_ENOMEM;
+  if (n > 65535) return WO_EUNSUPPORTED;
+  hipStream_t hs = (hipStream_t)stream;
+  char* w = (char*)ws;
+  DevOptics* dopt = (DevOptics*)(w + L.opt);
+  TuneState* tst = (TuneState*)(w + L.st);
+  double* pp = (double*)(w + L.pp);
+  double* lp = (double*)(w + L.lp);
+  double* dp = (double*)(w + L.dp);
+  double* gp = (double*)(w + L.gp);
+  double* ip = (double*)(w + L.ip);
+  float2* ab = (float2*)(w + L.ab);
+  float2* bank = (float2*)(w + L.bank);
+  float2* D = (float2*)(w + L.D);
+  float2* G = (float2*)(w + L.G);
+  Coupling* cpl = is_pol5(s) ? (Coupling*)(w + L.cpl) : nullptr;
+  {
+    std::vector<DevOptics> h(n);
+    std::vector<TuneState> t(n);
+    std::vector<Coupling> hc(n);
+    for (int i = 0; i < n; ++i) {
+      h[i] = dev_optics(o[i]);
+      memset(&t[i], 0, sizeof(TuneState));
+      t[i].band_count = 1.0;   // no loss of its own: the loss partials are zero
+      t[i].eta = eta;
+      if (cpl) hc[i] = coupling_of(o[i].swing);
+    }
+    WO_TRY(launch_set_params(dopt, h.data(), n, hs));
+    WO_TRY(launch_set_tune(tst, t.data(), n, hs));
+    if (cpl) WO_TRY(launch_set_coupling(cpl, hc.data(), n, hs));
+  }
+  Sampling sm = sampling_of(o);
+  for (int i = 0; i < n; ++i) sm.aberrated |= aberrated(o[i]) ? 1 : 0;
+  const long Z = s.Z, Y = s.Y, X = s.X, Xh = s.Xh, plane = Y * Xh;
+  const int C = s.C, P = s.P;
+  const double nfull = (double)Z * Y * X;
+  WO_TRY(hipMemsetAsync(lp, 0, (size_t)n * loss_blocks(sm) * sizeof(double), hs));
+  // the label-free pair at these optics, per plane then along Z: [v][Z][2][Y][Xh]
+  WO_TRY(launch_tf_fields_y(dopt, sm, n, ab, pp, hs, &sup));
+  WO_TRY(launch_tf_rows_labelfree(pp, sm, n, ab, bank, 2 * Z * plane, plane, 2 * plane, hs, &sup));
+  WO_TRY(launch_cols(bank, (int)Y, Xh, 2 * Z, 2 * Z, n, -1.f, hs, "k_cols_y_tf"));
+  WO_TRY(launch_cols(bank, (int)Z, 2 * plane, 1, 1, n, -1.f, hs, "k_cols_z_tf"));
+  // spectra of the data and of dL/df
+  WO_TRY(launch_rows_r2c(d, D, (int)X, RowGroups{C * Z * Y, C * Z * Y, C * Z * Y, n}, hs));
+  WO_TRY(launch_cols(D, (int)Y, Xh, C * Z, C * Z, n, -1.f, hs, "k_cols_y_fwd"));
+  WO_TRY(launch_cols(D, (int)Z, plane, C, C, n, -1.f, hs, "k_cols_z_fwd"));
+  WO_TRY(launch_rows_r2c(dL_df, G, (int)X, RowGroups{P * Z * Y, P * Z * Y, P * Z * Y, n}, hs));
+  WO_TRY(launch_cols(G, (int)Y, Xh, P * Z, P * Z, n, -1.f, hs, "k_cols_y_fwd"));
+  WO_TRY(launch_cols(G, (int)Z, plane, P, P, n, -1.f, hs, "k_cols_z_fwd"));
+  // dL/dH* of the pair per frequency (and H Y, the spectrum of dL/dd)
+  WO_TRY(launch_recon_grad(bank, D, G, b, cpl, sm, n, (float)eta, nfull, dL_dd_out ? 1 : 0, hs));
+  if (dL_dtheta_out) {
+    // per-plane 2D gradients (the adjoint of the Z transform), then the
+    // per-plane reverse mode through the synthesis shared with the thin model
+    WO_TRY(launch_cols(bank, (int)Z, 2 * plane, 1, 1, n, 1.f, hs, "k_cols_z_grad"));
+    WO_TRY(launch_cols(bank, (int)Y, Xh, 2 * Z, 2 * Z, n, 1.f, hs, "k_cols_y_grad"));
+    WO_TRY(launch_tf_rows_bwd(pp, sm, n, ab, bank, dp, hs, &sup));
+    WO_TRY(launch_tf_grad_y(dopt, sm, n, ab, gp, ip, hs, &sup));
+    WO_TRY(launch_adam(dopt, tst, sm, n, pp, lp, dp, gp, ip, 0, hs, &sup));
+  }
+  if (dL_dd_out) {
+    WO_TRY(launch_cols(D, (int)Z, plane, C, C, n, 1.f, hs, "k_cols_z_inv"));
+    WO_TRY(launch_cols(D, (int)Y, Xh, C * Z, C * Z, n, 1.f, hs, "k_cols_y_inv"));
+    WO_TRY(launch_rows_c2r(D, dL_dd_out, (int)X, RowGroups{C * Z * Y, C * Z * Y, C * Z * Y, n},
+                           (float)(1.0 / nfull), hs));
+  }
+  if (dL_dtheta_out) {
+    std::vector<TuneState> t(n);
+    WO_TRY(hipMemcpyAsync(t.data(), tst, n * sizeof(TuneState), hipMemcpyDeviceToHost, hs));
+    WO_TRY(hipStreamSynchronize(hs));
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < 4; ++j) dL_dtheta_out[4 * i + j] = t[i].grad[j];
+  }
+  return WO_OK;
+}
 
 // ---------------------------------------------------------------- reconstruction without allocation
 //

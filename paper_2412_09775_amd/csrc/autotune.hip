@@ -122,6 +122,109 @@ long loss_blocks(const Sampling& sm) {
   return (M + 255) / 256;
 }
 
+// ------------------------------------------------------------------ gradient of a loss of the 3D reconstruction
+
+// One thread per 3D half-spectrum frequency (kz, m) of patch v (grid y).  bank:
+// [v][Z][2][M] the label-free pair after its Z transform (POL: the 5 x 4 bank is
+// pol5_entry(coupling, pair)); D: [v][C][Z][M] the data spectrum; G: [v][P][Z][M]
+// the spectrum of dL/df.  Per frequency, with x = D - N b delta,
+// M = H^H H (+ eta I), F = M^-1 H^H x, Y = M^-1 G, R = x - H F:
+//   dL/dH* = (R Y^H - H Y F^H) / (2N)   (dL/dF* = G / (2N))
+// overwrites the pair in bank (POL: its coefficients summed through the
+// coupling, dL/dH_phase* = sum_cp Re(kappa_cp) dL/dH_cp*, dL/dH_abs* with
+// Im(kappa_cp)), and, if want_dd, D by H Y, the spectrum of dL/dd.
+template <bool POL>
+__global__ __launch_bounds__(256) void k_recon_grad(float2* __restrict__ bank, float2* __restrict__ D,
+                                                    const float2* __restrict__ G,
+                                                    const float* __restrict__ bg,
+                                                    const Coupling* __restrict__ cpl, int Z, long M,
+                                                    float eta, float n_full, int want_dd) {
+  constexpr int C = POL ? 5 : 1, P = POL ? 4 : 2;
+  const long per = (long)Z * M;
+  const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long v = blockIdx.y;
+  if (gid >= per) return;
+  const int z = (int)(gid / M);
+  const long m = gid - (long)z * M;
+  float2* hp = bank + ((v * Z + z) * 2) * M + m;
+  const float2 u = hp[0], w = hp[M];
+  float2 H[C][P];
+#pragma unroll
+  for (int c = 0; c < C; ++c)
+#pragma unroll
+    for (int p = 0; p < P; ++p)
+      H[c][p] = POL ? pol5_entry(cpl[v].k[c][p][0], cpl[v].k[c][p][1], u, w) : (p == 0 ? u : w);
+  const bool dc = z == 0 && m == 0;
+  float2 x[C];
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    x[c] = D[((v * C + c) * Z + z) * M + m];
+    if (dc && bg) x[c].x -= n_full * bg[v * C + c];
+  }
+  float2 g[P], mm[P][P], r[P];
+#pragma unroll
+  for (int p = 0; p < P; ++p) {
+    g[p] = G[((v * P + p) * Z + z) * M + m];
+    r[p] = make_float2(0.f, 0.f);
+#pragma unroll
+    for (int q = 0; q <= p; ++q) mm[p][q] = make_float2(0.f, 0.f);
+  }
+#pragma unroll
+  for (int c = 0; c < C; ++c)
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+      r[p] = cadd(r[p], cmul(cconj(H[c][p]), x[c]));
+#pragma unroll
+      for (int q = 0; q <= p; ++q) mm[p][q] = cadd(mm[p][q], cmul(cconj(H[c][p]), H[c][q]));
+    }
+  float2 L[P][P], F[P], Yv[P];
+  float dinv[P];
+  chol_factor<P>(mm, eta, L, dinv);
+  chol_apply<P>(L, dinv, r, F);
+  chol_apply<P>(L, dinv, g, Yv);
+  const float s = 0.5f / n_full;
+  float2 pair[2] = {make_float2(0.f, 0.f), make_float2(0.f, 0.f)};
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    float2 R = x[c], HY = make_float2(0.f, 0.f);
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+      R = csub(R, cmul(H[c][p], F[p]));
+      HY = cadd(HY, cmul(H[c][p], Yv[p]));
+    }
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+      const float2 Wcp = cscale(csub(cmulconj(R, Yv[p]), cmulconj(HY, F[p])), s);
+      if (POL) {
+        pair[0] = cadd(pair[0], cscale(Wcp, cpl[v].k[c][p][0]));
+        pair[1] = cadd(pair[1], cscale(Wcp, cpl[v].k[c][p][1]));
+      } else {
+        pair[p] = Wcp;
+      }
+    }
+    if (want_dd) D[((v * C + c) * Z + z) * M + m] = HY;
+  }
+  hp[0] = pair[0];
+  hp[M] = pair[1];
+}
+
+hipError_t launch_recon_grad(float2* bank, float2* D, const float2* G, const float* bg, const Coupling* cpl,
+                             const Sampling& sm, int npatch, float eta, double n_full, int want_dd,
+                             hipStream_t s) {
+  const long M = (long)sm.ny * (sm.nx / 2 + 1);
+  const long per = (long)sm.nz * M;
+  const long blocks = (per + 255) / 256;
+  if (npatch < 1 || npatch > 65535 || blocks > 0x7fffffffL) return hipErrorInvalidValue;
+  ScopedTiming _t("k_recon_grad", s);
+  if (cpl)
+    hipLaunchKernelGGL(k_recon_grad<true>, dim3((unsigned)blocks, (unsigned)npatch), dim3(256), 0, s, bank,
+                       D, G, bg, cpl, sm.nz, M, eta, (float)n_full, want_dd);
+  else
+    hipLaunchKernelGGL(k_recon_grad<false>, dim3((unsigned)blocks, (unsigned)npatch), dim3(256), 0, s, bank,
+                       D, G, bg, cpl, sm.nz, M, eta, (float)n_full, want_dd);
+  return hipGetLastError();
+}
+
 // ------------------------------------------------------------------ backward rows
 
 // ab: [v][2][Z][Y][XC] (field 0 = a, 1 = b after the inverse Y pass, complex,
@@ -650,7 +753,8 @@ hipError_t launch_adam(DevOptics* opt, TuneState* st, const Sampling& sm, int nv
 
 // ------------------------------------------------------------------ best start
 
-// One thread per patch; ties keep the earliest start.
+// One thread per patch; ties keep the earliest start, and a start whose loss
+// is not finite is taken only when no start's is.
 __global__ __launch_bounds__(64) void k_pick_best(const DevOptics* __restrict__ opt,
                                                   const TuneState* __restrict__ st, int starts,
                                                   int npatch, DevOptics* __restrict__ ropt,
@@ -659,8 +763,10 @@ __global__ __launch_bounds__(64) void k_pick_best(const DevOptics* __restrict__ 
   if (i >= npatch) return;
   const long v0 = (long)i * starts;
   long best = v0;
-  for (int s = 1; s < starts; ++s)
-    if (st[v0 + s].loss < st[best].loss) best = v0 + s;
+  for (int s = 1; s < starts; ++s) {
+    const double lb = st[best].loss, ls = st[v0 + s].loss;
+    if (ls < lb || (!isfinite(lb) && isfinite(ls))) best = v0 + s;
+  }
   ropt[i] = opt[best];
   eta[i] = (float)st[v0].eta;
 }

@@ -456,6 +456,10 @@ struct DevOptics {
 // and property p: the values every kernel that forms the 5 x 4 bank uses.
 struct Coupling {
   float k[5][4][2];
+  // Gram constants of the 4 x 4 solve from the reduced bank, lower triangles
+  // (entry p (p + 1) / 2 + q, q <= p): A = Kr^T Kr, B = Ki^T Ki, S = G + G^T,
+  // D = G - G^T with G = Kr^T Ki, Kr = Re kappa, Ki = Im kappa (5 x 4 each)
+  float a[10], b[10], s[10], d[10];
 };
 
 // One entry of the polarisation bank from the label-free pair at a frequency:
@@ -466,6 +470,60 @@ struct Coupling {
 __device__ __forceinline__ float2 pol5_entry(float kr, float ki, float2 hp, float2 ha) {
 #pragma clang fp contract(off)
   return make_float2(kr * hp.x + ki * ha.x, kr * hp.y + ki * ha.y);
+}
+
+// Cholesky factor of M + eta I = L L^H for a Hermitian positive semi-definite
+// M given by its lower triangle (m[p][q], q <= p): L below the diagonal and
+// the reciprocals of its diagonal.
+template <int P>
+__device__ __forceinline__ void chol_factor(const float2 (&m)[P][P], float eta, float2 (&L)[P][P],
+                                            float (&dinv)[P]) {
+#pragma unroll
+  for (int j = 0; j < P; ++j) {
+    float d = m[j][j].x + eta;
+#pragma unroll
+    for (int k = 0; k < j; ++k) d -= L[j][k].x * L[j][k].x + L[j][k].y * L[j][k].y;
+    const float lj = sqrtf(fmaxf(d, 1e-37f));
+    dinv[j] = 1.f / lj;
+#pragma unroll
+    for (int i = j + 1; i < P; ++i) {
+      float2 v = m[i][j];
+#pragma unroll
+      for (int k = 0; k < j; ++k) v = csub(v, cmulconj(L[i][k], L[j][k]));
+      L[i][j] = cscale(v, dinv[j]);
+    }
+  }
+}
+
+// F = (L L^H)^-1 r by the two triangular solves.
+template <int P>
+__device__ __forceinline__ void chol_apply(const float2 (&L)[P][P], const float (&dinv)[P],
+                                           const float2 (&r)[P], float2 (&F)[P]) {
+  float2 y[P];
+#pragma unroll
+  for (int i = 0; i < P; ++i) {
+    float2 v = r[i];
+#pragma unroll
+    for (int k = 0; k < i; ++k) v = csub(v, cmul(L[i][k], y[k]));
+    y[i] = cscale(v, dinv[i]);
+  }
+#pragma unroll
+  for (int i = P - 1; i >= 0; --i) {
+    float2 v = y[i];
+#pragma unroll
+    for (int k = i + 1; k < P; ++k) v = csub(v, cmul(cconj(L[k][i]), F[k]));
+    F[i] = cscale(v, dinv[i]);
+  }
+}
+
+// (M + eta I) F = r.
+template <int P>
+__device__ __forceinline__ void chol_solve(const float2 (&m)[P][P], const float2 (&r)[P], float eta,
+                                           float2 (&F)[P]) {
+  float2 L[P][P];
+  float dinv[P];
+  chol_factor<P>(m, eta, L, dinv);
+  chol_apply<P>(L, dinv, r, F);
 }
 
 // Detection aberration W(p) in waves: sum of zern[j - 5] Z_j over Noll's

@@ -709,42 +709,49 @@ __device__ __forceinline__ void freq_op(float2* cell, long cs, HF H, int Crt, in
     const float den = m[0][0].x + eta;
     F[0] = den > 0.f ? cscale(r[0], 1.f / den) : make_float2(0.f, 0.f);
   } else {
-    // Cholesky M + eta I = L L^H, then two triangular solves
-    float2 L[P][P];
-    float dinv[P];
-#pragma unroll
-    for (int j = 0; j < P; ++j) {
-      float d = m[j][j].x + eta;
-#pragma unroll
-      for (int k = 0; k < j; ++k) d -= L[j][k].x * L[j][k].x + L[j][k].y * L[j][k].y;
-      const float lj = sqrtf(fmaxf(d, 1e-37f));
-      dinv[j] = 1.f / lj;
-#pragma unroll
-      for (int i = j + 1; i < P; ++i) {
-        float2 v = m[i][j];
-#pragma unroll
-        for (int k = 0; k < j; ++k) v = csub(v, cmulconj(L[i][k], L[j][k]));
-        L[i][j] = cscale(v, dinv[j]);
-      }
-    }
-    float2 y[P];
-#pragma unroll
-    for (int i = 0; i < P; ++i) {
-      float2 v = r[i];
-#pragma unroll
-      for (int k = 0; k < i; ++k) v = csub(v, cmul(L[i][k], y[k]));
-      y[i] = cscale(v, dinv[i]);
-    }
-#pragma unroll
-    for (int i = P - 1; i >= 0; --i) {
-      float2 v = y[i];
-#pragma unroll
-      for (int k = i + 1; k < P; ++k) v = csub(v, cmul(cconj(L[k][i]), F[k]));
-      F[i] = cscale(v, dinv[i]);
-    }
+    chol_solve<P>(m, r, eta, F);
   }
 #pragma unroll
   for (int p = 0; p < P; ++p) cell[p * cs] = cscale(F[p], inv_n);
+}
+
+// The polarisation solve from the reduced bank at one frequency: with
+// H_cp = Kr_cp u + Ki_cp v (u = H_phase, v = H_abs there), H^H H has the entries
+// A |u|^2 + B |v|^2 + S Re(conj(u) v) + i D Im(conj(u) v) (constants of the
+// coupling) and H^H x = conj(u) Kr^T x + conj(v) Ki^T x, so the 5 x 4 bank is
+// never formed.  Algebraically the solve of freq_op with that bank.
+__device__ __forceinline__ void pol5_solve(float2* cell, long cs, float2 u, float2 v,
+                                           const Coupling* __restrict__ cp, float eta,
+                                           const float* __restrict__ bg, bool dc, float n_full,
+                                           float inv_n) {
+  float2 yr[4], yi[4];
+#pragma unroll
+  for (int p = 0; p < 4; ++p) yr[p] = yi[p] = make_float2(0.f, 0.f);
+#pragma unroll
+  for (int c = 0; c < 5; ++c) {
+    float2 xc = cell[c * cs];
+    if (dc && bg) xc.x -= n_full * bg[c];
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+      yr[p] = cadd(yr[p], cscale(xc, cp->k[c][p][0]));
+      yi[p] = cadd(yi[p], cscale(xc, cp->k[c][p][1]));
+    }
+  }
+  const float uu = u.x * u.x + u.y * u.y, vv = v.x * v.x + v.y * v.y;
+  const float2 w = cmulconj(v, u);   // conj(u) v
+  float2 m[4][4], r[4], F[4];
+#pragma unroll
+  for (int p = 0; p < 4; ++p) {
+    r[p] = cadd(cmulconj(yr[p], u), cmulconj(yi[p], v));
+#pragma unroll
+    for (int q = 0; q <= p; ++q) {
+      const int e = p * (p + 1) / 2 + q;
+      m[p][q] = make_float2(cp->a[e] * uu + cp->b[e] * vv + cp->s[e] * w.x, cp->d[e] * w.y);
+    }
+  }
+  chol_solve<4>(m, r, eta, F);
+#pragma unroll
+  for (int p = 0; p < 4; ++p) cell[p * cs] = cscale(F[p], inv_n);
 }
 
 constexpr int kTfPrefetch = 8;   // transfer-function values a thread may hold in registers
@@ -871,11 +878,15 @@ __global__ __launch_bounds__(1024, NS > 0 ? 7 : 1) void k_zop(float2* __restrict
       if constexpr (RED) {
         const float2 hph = hp[0], hab = hp[ts];
         const float* kf = &cpl[patch].k[0][0][0];
-        freq_op<P, CT>(buf + (long)z * CH * W + w, W,
-                       [&](int c, int p) {
-                         return pol5_entry(kf[(c * P + p) * 2], kf[(c * P + p) * 2 + 1], hph, hab);
-                       },
-                       C, mode, eta, bp, z == 0 && dc_tile && w == 0, n_full, inv_n);
+        if (mode == kModeSolve)
+          pol5_solve(buf + (long)z * CH * W + w, W, hph, hab, cpl + patch, eta, bp,
+                     z == 0 && dc_tile && w == 0, n_full, inv_n);
+        else
+          freq_op<P, CT>(buf + (long)z * CH * W + w, W,
+                         [&](int c, int p) {
+                           return pol5_entry(kf[(c * P + p) * 2], kf[(c * P + p) * 2 + 1], hph, hab);
+                         },
+                         C, mode, eta, bp, z == 0 && dc_tile && w == 0, n_full, inv_n);
       } else {
         freq_op<P, CT>(buf + (long)z * CH * W + w, W,
                        [&](int c, int p) { return hp[(long)(c * P + p) * ts]; }, C, mode, eta, bp,

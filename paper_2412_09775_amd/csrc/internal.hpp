@@ -222,6 +222,13 @@ long pupil_tiles(const Sampling& sm, const LatSupport& ls);
 hipError_t launch_loss_grad(const DevOptics* opt, const TuneState* st, const Sampling& sm, int nv,
                             const float2* D, float2* bank, double* lpart, int data_div,
                             hipStream_t s);
+// Gradient of a loss of the 3D reconstruction per frequency (bank [v][Z][2][M]
+// the label-free pair after its Z transform, D [v][C][Z][M] the data spectrum,
+// G [v][P][Z][M] the spectrum of dL/df; cpl: the polarisation bank): the pair
+// becomes dL/dH*, and D the spectrum of dL/dd if want_dd.
+hipError_t launch_recon_grad(float2* bank, float2* D, const float2* G, const float* bg, const Coupling* cpl,
+                             const Sampling& sm, int npatch, float eta, double n_full, int want_dd,
+                             hipStream_t s);
 // The backward kernels and Adam take the fields' compact columns (sup; NULL:
 // every column), as the field kernel wrote them.
 hipError_t launch_tf_rows_bwd(const double* partials, const Sampling& sm, int nv, float2* ab,

@@ -41,7 +41,7 @@ hipError_t launch_set_params(DevOptics* dst, const DevOptics* host, int n, hipSt
 }
 
 struct CouplingBatch {
-  Coupling c[16];
+  Coupling c[8];
 };
 static_assert(sizeof(CouplingBatch) <= 3584, "kernel arguments are limited to 4 KiB");
 
@@ -51,9 +51,9 @@ __global__ void k_set_coupling(Coupling* dst, CouplingBatch b, int count) {
 }
 
 hipError_t launch_set_coupling(Coupling* dst, const Coupling* host, int n, hipStream_t s) {
-  for (int i0 = 0; i0 < n; i0 += 16) {
+  for (int i0 = 0; i0 < n; i0 += 8) {
     CouplingBatch b;
-    const int cnt = n - i0 < 16 ? n - i0 : 16;
+    const int cnt = n - i0 < 8 ? n - i0 : 8;
     for (int j = 0; j < cnt; ++j) b.c[j] = host[i0 + j];
     hipLaunchKernelGGL(k_set_coupling, dim3(1), dim3(64), 0, s, dst + i0, b, cnt);
     hipError_t e = hipGetLastError();

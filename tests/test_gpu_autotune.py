@@ -249,3 +249,26 @@ def test_adam_on_aberration_coefficients_matches_oracle(gpu_lib, problem):
     assert out[0].defocus == o.defocus and out[0].na_det == o.na_det
     assert np.all(np.abs(got - c) <= 0.02 * lr_z * iters + 1e-6)
     assert abs(loss[0] - L) / abs(L) < 1e-3
+
+
+@pytest.mark.parametrize("use_graph", [0, 1])
+def test_nonfinite_patch_is_reported_and_does_not_fail_the_batch(gpu_lib, problem, use_graph):
+    """A patch whose data hold a NaN (a condition forced from the host: every kernel
+    still runs to its end, the NaN only propagates through arithmetic) ends with
+    status WO_DIVERGED, keeps its starting optics and a NaN loss; the other patches
+    tune exactly as in a batch without it."""
+    import torch
+    starts, d, etas, nu_c = problem
+    bad = d.copy()
+    bad[1, 3, 10, 20] = np.nan
+    status = np.full(len(starts), 99, dtype=np.int32)
+    out, loss, _, _ = gpu_lib.autotune(starts, torch.from_numpy(bad).cuda(), etas, iters=5, lr=LR, lo=LO,
+                                       hi=HI, nu_c=nu_c, use_graph=use_graph, status=status)
+    ref, ref_loss, _, _ = gpu_lib.autotune(starts, torch.from_numpy(d).cuda(), etas, iters=5, lr=LR, lo=LO,
+                                           hi=HI, nu_c=nu_c, use_graph=use_graph)
+    assert list(status) == [0, gpu_lib.DIVERGED, 0]
+    assert np.isnan(loss[1])
+    assert out[1].defocus == starts[1].defocus and out[1].tilt_zenith == starts[1].tilt_zenith
+    for i in (0, 2):
+        assert loss[i] == ref_loss[i]
+        assert out[i].defocus == ref[i].defocus and out[i].tilt_zenith == ref[i].tilt_zenith

@@ -367,9 +367,13 @@ def test_pol5_full_bank_is_the_expansion_of_its_reduced_form(gpu_lib, torch, nam
 
 @pytest.mark.parametrize("name", POL5_BAND)
 def test_pol5_linear_calls_with_the_reduced_bank_equal_the_full_bank(gpu_lib, torch, name):
-    """wo_linear_band with the reduced polarisation bank (entries formed per
-    frequency in the fused Z pass) gives bit for bit the full-layout calls'
-    results, and the reconstruction is within 1e-4 of the oracle's."""
+    """wo_linear_band with the reduced polarisation bank: the forward model and the
+    adjoint (entries formed per frequency in the fused Z pass) give bit for bit the
+    full-layout calls' results; the reconstruction (its Gram matrix formed from the
+    pair and constants of the coupling, a different rounding order) is within 1e-4
+    of the oracle's, and within 2e-5 of the full-layout call: two FP32 solves of
+    one system differ by rounding (6e-8) amplified by cond(M + eta I) <= 1 + 1e3
+    at eta = 1e-3 sigma_max^2."""
     opts = CASES[name]
     print(f"[case] pol5 reduced linear {name}", flush=True)
     red = gpu_lib.transfer_function_band(opts)
@@ -392,7 +396,10 @@ def test_pol5_linear_calls_with_the_reduced_bank_equal_the_full_bank(gpu_lib, to
     dt = torch.from_numpy(np.stack(ds)).cuda()
     eta = eta_for(opts[0], banks[0])
     got = gpu_lib.linear_band(gpu_lib.OP_RECONSTRUCT, opts, red, dt, eta=eta, b=b)
-    assert torch.equal(got, gpu_lib.reconstruct(opts, full, dt, eta, b=b))
+    ref_full = gpu_lib.reconstruct(opts, full, dt, eta, b=b)
+    e_full = float(torch.linalg.vector_norm(got - ref_full) / torch.linalg.vector_norm(ref_full))
+    print(f"  reduced vs full-layout reconstruction rel L2 = {e_full:.3e}")
+    assert e_full < 2e-5
     for i in range(len(opts)):
         ref = linear.reconstruct(banks[i], ds[i], b[i].cpu().numpy().astype(np.float64), eta)
         err = rel_l2(got[i].cpu().numpy(), ref)
