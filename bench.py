@@ -176,7 +176,8 @@ def summarise_trace(trace_dir, command, title):
            f"source_sha1 {source_sha1()}",
            "kernel\tgrid\tcalls\tavg_us\ttotal_us"]
     for (k, g), (c, t) in sorted(agg.items(), key=lambda kv: -kv[1][1]):
-        out.append(f"{k}\t{g}\t{c}\t{t / c:.1f}\t{t:.1f}")
+        if k.startswith("wo::"):     # the library's kernels (not the input generation's)
+            out.append(f"{k}\t{g}\t{c}\t{t / c:.1f}\t{t:.1f}")
     return "\n".join(out) + "\n"
 
 
@@ -218,12 +219,54 @@ def summarise_counters(fetch_dir, write_dir, commands, title):
             f"source_sha1 {source_sha1()}",
             "kernel\tgrid\tFETCH_KiB\tWRITE_KiB\tscaled_MB"]
     for key in sorted(set(seq_f) & set(seq_w)):
-        if "copyBuffer" in key[0] or key[0].startswith("at::") or "elementwise" in key[0]:
+        if not key[0].startswith("wo::"):     # the library's kernels (not the input generation's)
             continue
         f = sum(seq_f[key]) / len(seq_f[key])
         w = sum(seq_w[key]) / len(seq_w[key])
         mb = (f * sf + w * sw) * 1024 / 1e6
         out.append(f"{key[0]}\t{key[1]}\t{f:.1f}\t{w:.1f}\t{mb:.1f}")
+    return "\n".join(out) + "\n"
+
+
+def summarise_sq(dirs, commands, title):
+    """Per-dispatch averages of the SQ counters of one or more rocprofv3 --pmc CSV
+    directories for the library's kernels, with the ratios read from them:
+    VALU and LDS instructions per wave, the fraction of wave-cycles issuing VALU
+    work (SQ_ACTIVE_INST_VALU / SQ_WAVE_CYCLES), the fraction waiting on any
+    instruction (SQ_WAIT_INST_ANY / SQ_WAVE_CYCLES) and LDS bank-conflict cycles
+    per LDS instruction."""
+    import csv
+    import glob
+    from collections import defaultdict
+    vals = defaultdict(lambda: defaultdict(list))
+    for d in dirs:
+        for path in glob.glob(os.path.join(d, "*counter_collection.csv")):
+            for r in csv.DictReader(open(path)):
+                k = (_symbol(r["Kernel_Name"]), int(r["Grid_Size"]))
+                vals[k][r["Counter_Name"]].append(float(r["Counter_Value"]))
+    names = sorted({c for v in vals.values() for c in v})
+    out = [f"# SQ counters per dispatch: {title}"]
+    out += [f"# command: {c}" for c in commands]
+    out += ["# ratios: valu/wave = SQ_INSTS_VALU / SQ_WAVES; lds/wave = SQ_INSTS_LDS / SQ_WAVES; "
+            "valu_active = SQ_ACTIVE_INST_VALU / SQ_WAVE_CYCLES; wait_any = SQ_WAIT_INST_ANY / "
+            "SQ_WAVE_CYCLES; conflict/lds = SQ_LDS_BANK_CONFLICT / SQ_INSTS_LDS",
+            f"source_sha1 {source_sha1()}",
+            "kernel\tgrid\tdispatches\t" + "\t".join(names) +
+            "\tvalu/wave\tlds/wave\tvalu_active\twait_any\tconflict/lds"]
+
+    def ratio(a, b):
+        return f"{a / b:.3f}" if a is not None and b else "-"
+    for k in sorted(vals, key=lambda k: k[0]):
+        if not k[0].startswith("wo::"):
+            continue
+        m = {c: sum(v) / len(v) for c, v in vals[k].items()}
+        n = max(len(v) for v in vals[k].values())
+        g = m.get
+        out.append(f"{k[0]}\t{k[1]}\t{n}\t" + "\t".join(f"{m[c]:.4g}" if c in m else "-" for c in names) +
+                   f"\t{ratio(g('SQ_INSTS_VALU'), g('SQ_WAVES'))}\t{ratio(g('SQ_INSTS_LDS'), g('SQ_WAVES'))}"
+                   f"\t{ratio(g('SQ_ACTIVE_INST_VALU'), g('SQ_WAVE_CYCLES'))}"
+                   f"\t{ratio(g('SQ_WAIT_INST_ANY'), g('SQ_WAVE_CYCLES'))}"
+                   f"\t{ratio(g('SQ_LDS_BANK_CONFLICT'), g('SQ_INSTS_LDS'))}")
     return "\n".join(out) + "\n"
 
 
@@ -556,15 +599,20 @@ def main():
                     "summary of a rocprofv3 --kernel-trace directory to --summary-out")
     ap.add_argument("--summarise-counters", nargs=2, default=None, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="(no GPU) write the FETCH_SIZE/WRITE_SIZE summary to --summary-out")
+    ap.add_argument("--summarise-sq", nargs="+", default=None, metavar="PMC_DIR",
+                    help="(no GPU) write the SQ-counter summary of rocprofv3 --pmc directories")
     ap.add_argument("--summary-command", action="append", default=[],
                     help="command line recorded in the summary header (repeatable)")
     ap.add_argument("--summary-title", default="", help="workload named in the summary header")
     ap.add_argument("--summary-out", default="")
     args = ap.parse_args()
-    if args.summarise_trace or args.summarise_counters:
-        text = (summarise_trace(args.summarise_trace, " ".join(args.summary_command), args.summary_title)
-                if args.summarise_trace else
-                summarise_counters(*args.summarise_counters, args.summary_command, args.summary_title))
+    if args.summarise_trace or args.summarise_counters or args.summarise_sq:
+        if args.summarise_trace:
+            text = summarise_trace(args.summarise_trace, " ".join(args.summary_command), args.summary_title)
+        elif args.summarise_counters:
+            text = summarise_counters(*args.summarise_counters, args.summary_command, args.summary_title)
+        else:
+            text = summarise_sq(args.summarise_sq, args.summary_command, args.summary_title)
         if args.summary_out:
             open(args.summary_out, "w").write(text)
         else:
