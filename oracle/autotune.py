@@ -106,11 +106,36 @@ def _edge_slope(inside: np.ndarray, halfwidth: float) -> np.ndarray:
     return np.where((t > 0.0) & (t < 1.0), s, 0.0)
 
 
+def detection_tilt_derivatives(o: op.Optics):
+    """dP/d(det_tilt) and dP/d(det_azimuth) of the tilted detection cap (R20):
+    P = edge(NA_det/lambda0 - |p'|), |p'| = sqrt(k_m^2 - (k . a)^2), so
+    d|p'| = -(k . a)(k . da)/|p'| (zero for the hard edge)."""
+    fy, fx = op.lateral_frequencies(o)
+    hw = o.edge_width * o.dnu
+    pp2, ka = op.detection_lateral_distance_sq(o)
+    pp = np.sqrt(np.maximum(pp2, 0.0))
+    kz = np.sqrt(np.maximum(o.k_medium ** 2 - fy * fy - fx * fx, 0.0))
+    on = (fy * fy + fx * fx < o.k_medium ** 2) & (ka > 0.0)
+    sl = np.where(on, _edge_slope(o.na_det / o.wavelength - pp, hw), 0.0)
+    t, az = o.det_tilt, o.det_azimuth
+    da_dt = (math.cos(t) * math.sin(az), math.cos(t) * math.cos(az), -math.sin(t))
+    da_daz = (math.sin(t) * math.cos(az), -math.sin(t) * math.sin(az), 0.0)
+    out = []
+    for da in (da_dt, da_daz):
+        kda = fy * da[0] + fx * da[1] + kz * da[2]
+        with np.errstate(invalid="ignore", divide="ignore"):
+            dpp = np.where(pp > 0, -ka * kda / pp, 0.0)
+        out.append(-sl * dpp)
+    return out[0], out[1]
+
+
 def pupil_derivatives(o: op.Optics):
     """S, P and their partial derivatives w.r.t. (na_det, tilt_zenith, tilt_azimuth)."""
     fy, fx = op.lateral_frequencies(o)
     hw = o.edge_width * o.dnu
     rp = np.sqrt(fy * fy + fx * fx)
+    if o.det_tilt != 0.0:   # the lateral distance in the tilted frame (R20)
+        rp = np.sqrt(np.maximum(op.detection_lateral_distance_sq(o)[0], 0.0))
     P = op.detection_pupil(o)
     dP_dna = _edge_slope(o.na_det / o.wavelength - rp, hw) / o.wavelength
     cy, cx = op.source_centre(o)
@@ -166,11 +191,12 @@ def loss_and_gradient(o: op.Optics, d: np.ndarray, eta: float, nu_c: float):
     HY = np.einsum("ncp,np->nc", Hn, Yv)
     GH = r[:, :, None] * np.conj(Yv)[:, None, :] - HY[:, :, None] * np.conj(Fn)[:, None, :]
     GH = np.moveaxis(GH, 0, 2).reshape(Z, 2, Y, X)
-    return L, _pair_gradient_to_theta(o, zs, GH, a, b)
+    return L, _pair_gradient_to_theta(o, zs, GH, a, b)[:4]
 
 
 def _pair_gradient_to_theta(o: op.Optics, zs, GH: np.ndarray, a: np.ndarray, b: np.ndarray) -> np.ndarray:
-    """dL/dtheta from the gradient GH = dL/dH_z* (Z, 2, Y, X) of the per-plane 2D
+    """dL/dtheta (defocus, na_det, tilt_zenith, tilt_azimuth, det_tilt,
+    det_azimuth) from the gradient GH = dL/dH_z* (Z, 2, Y, X) of the per-plane 2D
     label-free pair H_z = [fft2(2 Re c_z), fft2(-2 Im c_z)] at the planes zs,
     c_z = (N / I_bg) b_z conj(a_z), a_z, b_z the inverse 2D transforms of the
     direct and scattered arms (Table 1's label-free row), by reverse mode
@@ -178,6 +204,7 @@ def _pair_gradient_to_theta(o: op.Optics, zs, GH: np.ndarray, a: np.ndarray, b: 
     Y, X = o.ny, o.nx
     N = Y * X
     S, P, dP_dna, dS_dzen, dS_daz = pupil_derivatives(o)
+    dP_dt, dP_daz = detection_tilt_derivatives(o)
     g = op.greens_spectrum(o)
     kz = op.axial_wavenumber(o)
     ibg = float(np.sum(S * P * P))
@@ -189,7 +216,7 @@ def _pair_gradient_to_theta(o: op.Optics, zs, GH: np.ndarray, a: np.ndarray, b: 
     ds_term = 4.0 * np.real(np.sum(Gam * b * np.conj(a)))
     UB = sfft.ifft2(s * Gam * np.conj(a), axes=(-2, -1))     # dL = 4 Re sum dB * UB
     UA = sfft.ifft2(s * np.conj(Gam * b), axes=(-2, -1))     # dL = 4 Re sum dA * UA
-    grad = np.zeros(4)
+    grad = np.zeros(6)
     for k, z in enumerate(zs):
         prop = np.exp(2j * np.pi * kz * (z - o.defocus))
         A = S * P * prop
@@ -199,8 +226,11 @@ def _pair_gradient_to_theta(o: op.Optics, zs, GH: np.ndarray, a: np.ndarray, b: 
         grad[1] += 4.0 * np.real(np.sum(UB[k] * dP_dna * g * prop) + np.sum(UA[k] * S * dP_dna * prop))
         grad[2] += 4.0 * np.real(np.sum(UA[k] * dS_dzen * P * prop))
         grad[3] += 4.0 * np.real(np.sum(UA[k] * dS_daz * P * prop))
+        grad[4] += 4.0 * np.real(np.sum(UB[k] * dP_dt * g * prop) + np.sum(UA[k] * S * dP_dt * prop))
+        grad[5] += 4.0 * np.real(np.sum(UB[k] * dP_daz * g * prop) + np.sum(UA[k] * S * dP_daz * prop))
     # s = N / I_bg, I_bg = sum S P^2
-    dibg = np.array([0.0, np.sum(2.0 * S * P * dP_dna), np.sum(dS_dzen * P * P), np.sum(dS_daz * P * P)])
+    dibg = np.array([0.0, np.sum(2.0 * S * P * dP_dna), np.sum(dS_dzen * P * P), np.sum(dS_daz * P * P),
+                     np.sum(2.0 * S * P * dP_dt), np.sum(2.0 * S * P * dP_daz)])
     grad += ds_term * (-s / ibg) * dibg
     return grad
 
@@ -215,17 +245,25 @@ def recon_objective(o: op.Optics, d: np.ndarray, eta: float, w: np.ndarray, b=No
     return float(np.sum(np.asarray(w, dtype=np.float64) * f))
 
 
-def recon_fd_gradient(o: op.Optics, d, eta, w, steps, b=None, which=(0, 1, 2, 3)) -> np.ndarray:
-    """dL/dtheta of recon_objective by central differences with one Richardson step."""
-    th = theta_of(o)
-    g = np.zeros(4)
+PARAMS6 = PARAMS + ("det_tilt", "det_azimuth")
+
+
+def with_theta6(o: op.Optics, theta) -> op.Optics:
+    return with_theta(o, theta).replace(det_tilt=float(theta[4]), det_azimuth=float(theta[5]))
+
+
+def recon_fd_gradient(o: op.Optics, d, eta, w, steps, b=None, which=(0, 1, 2, 3, 4, 5)) -> np.ndarray:
+    """dL/dtheta (the six components of PARAMS6) of recon_objective by central
+    differences with one Richardson step (steps: one per component)."""
+    th = np.concatenate([theta_of(o), [o.det_tilt, o.det_azimuth]])
+    g = np.zeros(6)
     for j in which:
         def cd(h):
             tp, tm = th.copy(), th.copy()
             tp[j] += h
             tm[j] -= h
-            return (recon_objective(with_theta(o, tp), d, eta, w, b)
-                    - recon_objective(with_theta(o, tm), d, eta, w, b)) / (2 * h)
+            return (recon_objective(with_theta6(o, tp), d, eta, w, b)
+                    - recon_objective(with_theta6(o, tm), d, eta, w, b)) / (2 * h)
         h = steps[j]
         g[j] = (4.0 * cd(h / 2) - cd(h)) / 3.0
     return g
@@ -233,7 +271,7 @@ def recon_fd_gradient(o: op.Optics, d, eta, w, steps, b=None, which=(0, 1, 2, 3)
 
 def recon_gradient(o: op.Optics, d: np.ndarray, eta: float, w: np.ndarray, b=None):
     """Reverse mode for a loss L of the 3D reconstruction f given w = dL/df
-    (P, Z, Y, X): returns (dL/dtheta (4,), dL/dd (C, Z, Y, X)).  Label-free 3D and
+    (P, Z, Y, X): returns (dL/dtheta (6,) over PARAMS6, dL/dd (C, Z, Y, X)).  Label-free 3D and
     the 5 x 4 polarisation bank (whose entries are Re(kappa) H_phase +
     Im(kappa) H_abs of the label-free pair).
 

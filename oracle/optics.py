@@ -31,6 +31,20 @@ R18 Detection aberrations (Ext. Data Fig. 3b: Zernike coefficients enter
     p_x).  The phase multiplies the pupil wherever it appears (direct and
     scattered arms, fluorescence); the polynomials continue past rho = 1 into
     a soft edge.  I_bg = sum S |P|^2 is unchanged.
+R20 Oblique detection (Ext. Data Fig. light paths, panel b: the oblique
+    detection path; Results, neuromasts imaged with oblique and straight
+    detection): the detection objective's axis a is tilted from the sample's z
+    axis by the zenith angle det_tilt in the azimuth det_azimuth, a =
+    (sin t sin az, sin t cos az, cos t) in (y, x, z) (the source tilt's azimuth
+    convention).  The detection pupil is the cap of the shell within the
+    detection NA about a: P(p) = edge(NA_det/lambda0 - |p'|) with |p'|^2 =
+    k_m^2 - (k . a)^2 the lateral distance in the tilted frame, k = (p,
+    kz(p)), and k . a > 0; at det_tilt = 0 this is the disc.  The cap must
+    stay inside the shell: k_m sin(det_tilt + asin(NA_det/n)) plus the soft
+    edge below k_m.  The reconstruction stays on the sample grid (re-slicing
+    an oblique acquisition onto it is not part of the method's arithmetic).
+    The aberration polynomials are defined on the untilted pupil, so detection
+    tilt and aberrations are not combined.
 All arithmetic is float64 / complex128.
 """
 
@@ -69,6 +83,8 @@ class Optics:
     edge_width: float = 0.0    # soft pupil edge half-width in frequency pixels; 0 = hard
     swing: float = 0.1         # polarisation bank only
     zernike: tuple = ()        # detection aberration, waves, Noll j = 5, 6, ... (R18)
+    det_tilt: float = 0.0      # detection axis zenith angle, rad (R20)
+    det_azimuth: float = 0.0   # and its azimuth, rad
 
     def replace(self, **kw) -> "Optics":
         return dataclasses.replace(self, **kw)
@@ -126,10 +142,44 @@ def radius_disc(fy, fx, radius: float, halfwidth: float, cy=0.0, cx=0.0):
     return edge(radius - np.sqrt(r2), halfwidth)
 
 
-def detection_pupil(o: Optics) -> np.ndarray:
-    """P(p): disc of radius NA_det/lambda0 (Ext. Data Fig. 3b, calc_det_pupil)."""
+def detection_axis(o: Optics):
+    """Unit vector (ay, ax, az) of the detection axis (reading R20)."""
+    t, az = o.det_tilt, o.det_azimuth
+    return math.sin(t) * math.sin(az), math.sin(t) * math.cos(az), math.cos(t)
+
+
+def detection_lateral_distance_sq(o: Optics):
+    """(|p'|^2, k . a) on the lateral grid: the squared lateral distance of the
+    shell point k = (p, kz(p)) from the detection axis a, and k . a (R20)."""
     fy, fx = lateral_frequencies(o)
-    return radius_disc(fy, fx, o.na_det / o.wavelength, o.edge_width * o.dnu)
+    kz = np.sqrt(np.maximum(o.k_medium ** 2 - fy * fy - fx * fx, 0.0))
+    ay, ax, az = detection_axis(o)
+    ka = fy * ay + fx * ax + kz * az
+    return o.k_medium ** 2 - ka * ka, ka
+
+
+def detection_pupil(o: Optics) -> np.ndarray:
+    """P(p): disc of radius NA_det/lambda0 (Ext. Data Fig. 3b, calc_det_pupil); with
+    oblique detection the cap of that NA about the tilted detection axis (R20)."""
+    fy, fx = lateral_frequencies(o)
+    rd, hw = o.na_det / o.wavelength, o.edge_width * o.dnu
+    if o.det_tilt == 0.0:
+        return radius_disc(fy, fx, rd, hw)
+    pp2, ka = detection_lateral_distance_sq(o)
+    on_shell = fy * fy + fx * fx < o.k_medium ** 2
+    fwd = (ka > 0.0) & on_shell
+    if hw == 0.0:
+        return ((pp2 <= rd * rd) & fwd).astype(np.float64)
+    return np.where(fwd, edge(rd - np.sqrt(np.maximum(pp2, 0.0)), hw), 0.0)
+
+
+def detection_radius(o: Optics) -> float:
+    """Radius about p = 0 of a disc holding the detection pupil's support (without
+    the soft edge): NA_det/lambda0, or k_m sin(det_tilt + asin(NA_det/n)) (R20)."""
+    if o.det_tilt == 0.0:
+        return o.na_det / o.wavelength
+    a = abs(o.det_tilt) + math.asin(min(o.na_det / o.n_medium, 1.0))
+    return o.k_medium * (math.sin(a) if a < 0.5 * math.pi else 1.0)
 
 
 ZERNIKE_FIRST = 5     # Noll index of zernike[0]
@@ -272,19 +322,22 @@ def check_optics(o: Optics) -> None:
         raise ValueError("bad aperture")
     km = o.k_medium
     hw = o.edge_width * o.dnu
-    if o.na_det / o.wavelength + hw >= km:
+    rdet = detection_radius(o)
+    if rdet + hw >= km or abs(o.det_tilt) + math.asin(min(o.na_det / o.n_medium, 1.0)) >= 0.5 * math.pi:
         raise ValueError("detection pupil reaches the evanescent boundary")
+    if o.det_tilt != 0.0 and any(o.zernike):
+        raise ValueError("detection tilt with aberrations is not supported (R20)")
     qy, qx = source_centre(o)
     q0 = math.hypot(qy, qx)
     if o.model != FLUOR_3D and o.na_ill / o.wavelength + q0 + hw >= km:
         raise ValueError("illumination pupil reaches the evanescent boundary")
     nyq = min(0.5 / o.dx, 0.5 / o.dy)
     if o.model == FLUOR_3D:
-        lat = 2.0 * (o.na_det / o.wavelength + hw)
-        ax = km * (1.0 - math.sqrt(1.0 - ((o.na_det / o.wavelength + hw) / km) ** 2))
+        lat = 2.0 * (rdet + hw)
+        ax = km * (1.0 - math.sqrt(1.0 - ((rdet + hw) / km) ** 2))
     else:
-        lat = (o.na_det + o.na_ill) / o.wavelength + q0 + 2.0 * hw
-        kd = min(o.na_det / o.wavelength + hw, km)
+        lat = rdet + o.na_ill / o.wavelength + q0 + 2.0 * hw
+        kd = min(rdet + hw, km)
         ax = km - math.sqrt(km * km - kd * kd)
     if lat >= nyq:
         raise ValueError("lateral aliasing")
@@ -299,12 +352,13 @@ def hard_edge_margin(o: Optics) -> float:
     """
     fy, fx = lateral_frequencies(o)
     out = np.inf
-    for radius, (cy, cx) in (
-        (o.na_det / o.wavelength, (0.0, 0.0)),
-        (o.na_ill / o.wavelength, source_centre(o)),
-    ):
+    cy, cx = source_centre(o)
+    # (squared distance, edge radius): the detection pupil (its tilted cap, R20),
+    # then the source disc
+    pd2 = detection_lateral_distance_sq(o)[0] if o.det_tilt != 0.0 else fy * fy + fx * fx
+    for r2, radius in ((pd2, o.na_det / o.wavelength),
+                       ((fy - cy) ** 2 + (fx - cx) ** 2, o.na_ill / o.wavelength)):
         if radius <= 0:
             continue
-        r2 = (fy - cy) ** 2 + (fx - cx) ** 2
         out = min(out, float(np.min(np.abs(r2 - radius * radius))) / (radius * radius))
     return out

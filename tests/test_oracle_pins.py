@@ -559,7 +559,7 @@ def test_recon_gradient_matches_finite_differences(model):
     Fig. 3) against central differences of the plain definition L = <w, R_eta d>."""
     o, d, w, eta = _recon_case(model)
     grad, _ = at.recon_gradient(o, d, eta, w)
-    fd = at.recon_fd_gradient(o, d, eta, w, steps=(1e-5, 1e-5, 1e-5, 1e-5))
+    fd = at.recon_fd_gradient(o, d, eta, w, steps=(1e-5,) * 6)
     scale = np.max(np.abs(fd))
     assert np.max(np.abs(grad - fd)) < 1e-6 * scale, (grad, fd)
 
@@ -568,7 +568,7 @@ def test_recon_gradient_with_a_background_and_odd_depth():
     o, d, w, eta = _recon_case(op.LABELFREE_3D, seed=3, nz=5, defocus=-0.2, tilt_zenith=0.05)
     b = np.array([0.3])
     grad, _ = at.recon_gradient(o, d, eta, w, b=b)
-    fd = at.recon_fd_gradient(o, d, eta, w, steps=(1e-5,) * 4, b=b)
+    fd = at.recon_fd_gradient(o, d, eta, w, steps=(1e-5,) * 6, b=b)
     assert np.max(np.abs(grad - fd)) < 1e-6 * np.max(np.abs(fd))
 
 
@@ -581,3 +581,88 @@ def test_recon_data_gradient_is_the_transpose_of_the_reconstruction(model):
     lhs = float(np.sum(dd * e))
     rhs = float(np.sum(w * linear.reconstruct(tfm.transfer_function(o), e, None, eta)))
     assert abs(lhs - rhs) < 1e-10 * abs(rhs)
+
+
+# ---------------------------------------------------------------- oblique detection (R20)
+
+def test_untilted_detection_is_the_disc_for_every_azimuth():
+    for az in (0.0, 0.7, -2.1):
+        o = lf_optics(det_azimuth=az, edge_width=0.5)
+        fy, fx = op.lateral_frequencies(o)
+        assert np.array_equal(op.detection_pupil(o),
+                              op.radius_disc(fy, fx, o.na_det / o.wavelength, o.edge_width * o.dnu))
+
+
+def test_tilted_detection_cap_is_the_cone_about_the_axis():
+    """Hard cap: a shell point is inside exactly when the angle between k = (p, kz)
+    and the tilted axis is at most asin(NA_det / n) (the angle computed directly)."""
+    o = lf_optics(ny=32, nx=32, na_det=0.7, det_tilt=0.35, det_azimuth=0.9)
+    P = op.detection_pupil(o)
+    fy, fx = op.lateral_frequencies(o)
+    kz = op.axial_wavenumber(o)
+    ay, ax, az = op.detection_axis(o)
+    cosang = np.clip((fy * ay + fx * ax + kz * az) / o.k_medium, -1.0, 1.0)
+    ang = np.arccos(cosang)
+    alpha = math.asin(o.na_det / o.n_medium)
+    on = fy * fy + fx * fx < o.k_medium ** 2
+    assert np.all(ang[on & (P > 0)] <= alpha + 1e-9)
+    assert np.all(ang[on & (P == 0)] > alpha - 1e-9)
+    assert P.sum() > 10
+    # the cap is displaced towards the tilt: its centroid lies along (sin az, cos az)
+    cy, cx = np.sum(P * fy) / P.sum(), np.sum(P * fx) / P.sum()
+    assert cy * math.cos(o.det_azimuth) - cx * math.sin(o.det_azimuth) == pytest.approx(0.0, abs=0.06)
+    assert cy * math.sin(o.det_azimuth) + cx * math.cos(o.det_azimuth) > 0.5
+
+
+def test_detection_tilt_azimuth_rotates_the_bank():
+    """On a square grid, turning the detection azimuth by pi/2 turns the transfer
+    function by pi/2 (odd grid sizes: every frequency has its rotated partner)."""
+    base = dict(model=op.LABELFREE_3D, nz=5, ny=15, nx=15, dz=0.25, dy=0.13, dx=0.13, wavelength=0.532,
+                na_ill=0.0, na_det=0.8, n_medium=1.33, det_tilt=0.3, det_azimuth=0.2, edge_width=0.5)
+    o1 = op.Optics(**base)
+    o2 = o1.replace(det_azimuth=0.2 + math.pi / 2)
+    h1, h2 = tfm.labelfree_3d(o1), tfm.labelfree_3d(o2)
+    # a = (sin t sin az, sin t cos az) in (y, x): az + pi/2 turns a by R: (y, x) -> (x, -y),
+    # so H2(f) = H1(R^-1 f) with R^-1 (y, x) = (-x, y)
+    n = o1.ny
+    iy, ix = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    for k in range(2):
+        rot = h1[k][:, (-ix) % n, iy]
+        assert np.allclose(h2[k], rot, atol=1e-10 * np.abs(h1[k]).max())
+
+
+def test_tilted_detection_point_response_is_abbe_source_sum():
+    o = lf_optics(ny=8, nx=8, dx=0.13, dy=0.13, na_det=0.7, na_ill=0.4, defocus=0.1, det_tilt=0.3,
+                  det_azimuth=0.6, edge_width=0.5)
+    got = tfm.labelfree_point_response(o)
+    ref = abbe_point_response(o)
+    assert np.allclose(got, ref, atol=1e-12 * np.abs(ref).max())
+
+
+def test_tilted_detection_fluorescence_otf_is_pupil_autocorrelation():
+    o = fl_optics(nz=4, ny=8, nx=8, dx=0.13, dy=0.13, na_det=0.8, defocus=0.1, det_tilt=0.3, det_azimuth=-0.4)
+    P = op.detection_pupil(o)
+    h = np.stack([np.fft.ifft2(P * op.propagator(o, z)) for z in op.z_planes_3d(o)])
+    P3 = direct_dft(h)
+    ref = np.zeros(h.shape, dtype=np.complex128)
+    for nu in np.ndindex(h.shape):
+        ref[nu] = np.sum(P3 * np.conj(np.roll(P3, shift=nu, axis=(0, 1, 2)))) / h.size
+    ref /= ref[0, 0, 0]
+    assert np.allclose(tfm.fluorescence_3d(o), ref, atol=1e-12)
+
+
+@pytest.mark.parametrize("model", [op.LABELFREE_3D, op.POL5_3D])
+def test_recon_gradient_with_tilted_detection_matches_finite_differences(model):
+    o, d, w, eta = _recon_case(model, seed=7, det_tilt=0.25, det_azimuth=0.8, na_det=0.7)
+    grad, _ = at.recon_gradient(o, d, eta, w)
+    fd = at.recon_fd_gradient(o, d, eta, w, steps=(1e-5,) * 6)
+    assert np.max(np.abs(grad - fd)) < 1e-6 * np.max(np.abs(fd)), (grad, fd)
+    assert abs(fd[4]) > 1e-3 * np.max(np.abs(fd)) and abs(fd[5]) > 1e-3 * np.max(np.abs(fd))
+
+
+def test_detection_cap_must_stay_inside_the_shell():
+    o = lf_optics(na_det=1.0, det_tilt=0.9)          # asin(1/1.33) + 0.9 > pi/2
+    with pytest.raises(ValueError):
+        op.check_optics(o)
+    with pytest.raises(ValueError):
+        op.check_optics(lf_optics(det_tilt=0.2, zernike=(0.1,)))
