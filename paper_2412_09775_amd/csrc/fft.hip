@@ -806,12 +806,15 @@ __global__ __launch_bounds__(1024, NS > 0 ? 7 : 1) void k_zop(float2* __restrict
   // data tile is loaded and transformed.  Frequency f = tid + i * nthr.
   const int nfreq = Zc * W;
   const int fpt = (nfreq + nthr - 1) / nthr;
-  const bool prefetch = !RED && CT == 1 && P * fpt <= kTfPrefetch;
-  float2 hreg[kTfPrefetch];
+  // entries of the bank a frequency reads: P (one channel) or the pair (reduced)
+  constexpr int NE = RED ? 2 : P;
+  constexpr int NPF = RED ? 4 : kTfPrefetch;   // registers for the prefetched entries
+  const bool prefetch = (RED || CT == 1) && NE * fpt <= NPF;
+  float2 hreg[NPF];
   if (prefetch) {
 #pragma unroll
-    for (int j = 0; j < kTfPrefetch; ++j) {
-      const int i = j / P, cp = j - i * P;
+    for (int j = 0; j < NPF; ++j) {
+      const int i = j / NE, cp = j - i * NE;
       const int f = tid + i * nthr;
       if (i < fpt && f < nfreq) {
         const int z = f >> wsh, w = f & (W - 1);
@@ -859,14 +862,28 @@ __global__ __launch_bounds__(1024, NS > 0 ? 7 : 1) void k_zop(float2* __restrict
   }
   if (prefetch) {
 #pragma unroll
-    for (int i = 0; i < kTfPrefetch; ++i) {
+    for (int i = 0; i < NPF / NE; ++i) {
       const int f = tid + i * nthr;
       if (i < fpt && f < nfreq) {
         const int z = f >> wsh, w = f & (W - 1);
         if (w < weff) {
-          freq_op<P, 1>(buf + (long)z * CH * W + w, W,
-                        [&](int c, int p) { return hreg[i * P + p]; }, C, mode, eta, bp,
-                        z == 0 && dc_tile && w == 0, n_full, inv_n);
+          const bool dcf = z == 0 && dc_tile && w == 0;
+          if constexpr (RED) {
+            const float2 hph = hreg[i * 2], hab = hreg[i * 2 + 1];
+            const float* kf = &cpl[patch].k[0][0][0];
+            if (mode == kModeSolve)
+              pol5_solve(buf + (long)z * CH * W + w, W, hph, hab, cpl + patch, eta, bp, dcf, n_full, inv_n);
+            else
+              freq_op<P, CT>(buf + (long)z * CH * W + w, W,
+                             [&](int c, int p) {
+                               return pol5_entry(kf[(c * P + p) * 2], kf[(c * P + p) * 2 + 1], hph, hab);
+                             },
+                             C, mode, eta, bp, dcf, n_full, inv_n);
+          } else {
+            freq_op<P, 1>(buf + (long)z * CH * W + w, W,
+                          [&](int c, int p) { return hreg[i * P + p]; }, C, mode, eta, bp, dcf, n_full,
+                          inv_n);
+          }
         }
       }
     }
@@ -956,8 +973,13 @@ static bool zop_choice_ok(int Z, int CH, const FftChoice& c) {
          (long)(Z + elems) * (long)sizeof(float2) <= lds_limit_bytes() && c.plan >= 0 && c.plan <= 3;
 }
 
+// At most 4096 elements per workgroup (8 per thread, 512 threads): the pass
+// waits on its loads and stores between short bursts of arithmetic, and
+// smaller workgroups let more of them share a CU (5 channels x 64 planes:
+// 8 columns 249 us, 16 columns 282 us on the 64x1024x1024 volume).
 static FftChoice zop_default(int Z, int CH) {
-  const int W = tile_width(Z, CH);
+  int W = tile_width(Z, CH);
+  while (W > 1 && (long)W * Z * CH > 4096) W /= 2;
   return FftChoice{W, threads_for((long)CH * Z * W), 0};
 }
 
