@@ -118,6 +118,17 @@ typedef struct wo_optics {
                               (NA_det/lambda0), phi = atan2(p_y, p_x) (Methods,
                               detection-parameter branch: Zernike coefficients in
                               calc_det_pupil).  Zero: no aberration. */
+  /* Oblique detection (the light-path figure's oblique detection path;
+     neuromasts imaged with oblique and straight detection): the detection
+     axis is tilted by det_tilt (zenith, rad) in the azimuth det_azimuth,
+     a = (sin t sin az, sin t cos az, cos t) in (y, x, z), and the detection
+     pupil is the cap of the shell within NA_det about it:
+     P = edge(NA_det/lambda0 - |p'|), |p'|^2 = (n/lambda0)^2 - (k . a)^2,
+     k = (p, kz(p)), k . a > 0 (the disc at det_tilt = 0).  The cap must stay
+     inside the shell (WO_EINVAL); not combined with zernike
+     (WO_EUNSUPPORTED).  The data stay on the sample grid. */
+  double det_tilt;
+  double det_azimuth;
 } wo_optics;
 
 /* Bank shape of the model: *C channels, *P properties, *dims spatial
@@ -231,19 +242,20 @@ int wo_adjoint(const wo_optics* o, int32_t n, const void* tf, const float* r, fl
  * "Physics-guided ML auto-tunes multi-contrast blind deconvolution").  Given
  * dL/df of the reconstruction f = wo_reconstruct(transfer function of o, d, b,
  * eta), returns dL/dtheta for theta = (defocus, na_det, tilt_zenith,
- * tilt_azimuth) of each patch and dL/dd.  The transfer function is recomputed
+ * tilt_azimuth, det_tilt, det_azimuth) of each patch and dL/dd.  The transfer function is recomputed
  * from o (not stored), the same bank wo_transfer_function writes.  Per 3D
  * frequency, with x = D - N b delta, M = H^H H + eta I, F = M^-1 H^H x:
  * dL/dF* = FFT3(dL/df) / (2N), Y = M^-1 dL/dF*, dL/dH* = (x - H F) Y^H - H Y F^H,
  * dL/dd = Re IFFT3(2N H Y); dL/dH* then goes back through the 3D transform of
  * the per-plane label-free pair (whose adjoint along z is the unnormalised
  * inverse DFT), the correlation of the two arms and the pupils (analytic
- * derivatives of the soft edge; hard edges give no NA or tilt gradient).
+ * derivatives of the soft edge; hard edges give no NA or tilt gradient; the
+ * detection axis enters through the tilted detection pupil).
  * Aberrated optics are accepted (dL/dNA includes the aberration's NA
  * dependence).  Models LABELFREE_3D and POL5_3D (whose 5 x 4 bank is the
  * coupling's mix of the pair); others WO_EUNSUPPORTED.
  * d: device [n][C][vol]; b: device [n][C] or NULL; eta > 0; dL_df: device
- * [n][P][vol]; dL_dtheta_out: host [n][4] or NULL; dL_dd_out: device
+ * [n][P][vol]; dL_dtheta_out: host [n][6] or NULL; dL_dd_out: device
  * [n][C][vol] or NULL (not both NULL).  Workspace of
  * wo_reconstruct_grad_workspace_size bytes (0: unsupported model).
  * Synchronises `stream` when dL_dtheta_out is not NULL. */

@@ -55,7 +55,8 @@ N_ZERNIKE = 7   # Noll j = 5..11
 class WoOptics(ctypes.Structure):
     _fields_ = ([("model", ctypes.c_int32), ("nz", ctypes.c_int32), ("ny", ctypes.c_int32),
                  ("nx", ctypes.c_int32)] + [(f, ctypes.c_double) for f in _FIELDS[4:]]
-                + [("zernike", ctypes.c_double * N_ZERNIKE)])
+                + [("zernike", ctypes.c_double * N_ZERNIKE)]
+                + [("det_tilt", ctypes.c_double), ("det_azimuth", ctypes.c_double)])
 
 
 @dataclasses.dataclass
@@ -79,6 +80,8 @@ class Optics:
     edge_width: float = 0.0
     swing: float = 0.1
     zernike: tuple = ()   # detection aberration, waves, Noll j = 5..11 (up to 7 values)
+    det_tilt: float = 0.0       # oblique detection: detection axis zenith, rad
+    det_azimuth: float = 0.0    # and azimuth, rad
 
 
 class WoAutotuneOpts(ctypes.Structure):
@@ -197,6 +200,9 @@ def optics_array(optics) -> ctypes.Array:
             raise ValueError(f"at most {N_ZERNIKE} Zernike coefficients (Noll 5..11)")
         for j in range(N_ZERNIKE):
             arr[i].zernike[j] = float(z[j]) if j < len(z) else 0.0
+        for f in ("det_tilt", "det_azimuth"):
+            v = o.get(f, 0.0) if isinstance(o, dict) else getattr(o, f, 0.0)
+            setattr(arr[i], f, float(v))
     return arr
 
 
@@ -335,7 +341,7 @@ def reconstruct_noalloc(optics, tf, d, eta, b=None, out=None, stream=None):
 def reconstruct_grad(optics, d, eta, dL_df, b=None, want_theta=True, want_data=True, ws=None,
                      stream=None):
     """Gradient of a loss of the reconstruction (``wo_reconstruct_grad``): returns
-    (dL/dtheta numpy (n, 4) or None, dL/dd tensor (n, C, *vol) or None)."""
+    (dL/dtheta numpy (n, 6) over PARAMS6 or None, dL/dd tensor (n, C, *vol) or None)."""
     import numpy as np
     import torch
     lib = load()
@@ -346,7 +352,7 @@ def reconstruct_grad(optics, d, eta, dL_df, b=None, want_theta=True, want_data=T
         raise WoError(-2, "wo_reconstruct_grad_workspace_size")
     if ws is None or ws.numel() < need:
         ws = torch.empty(need, dtype=torch.uint8, device=d.device)
-    gth = np.zeros((n, 4)) if want_theta else None
+    gth = np.zeros((n, 6)) if want_theta else None
     gd = torch.empty_like(d) if want_data else None
     _check(lib.wo_reconstruct_grad(arr, n, _ptr(d.contiguous()), _ptr(b), ctypes.c_double(eta),
                                    _ptr(dL_df.contiguous()),
@@ -438,6 +444,7 @@ def timing_report() -> dict:
 # ---------------------------------------------------------------- auto-tune (thin model)
 
 PARAMS = ("defocus", "na_det", "tilt_zenith", "tilt_azimuth")
+PARAMS6 = PARAMS + ("det_tilt", "det_azimuth")
 PAPER_LR = (0.02, 0.005, 0.005, 0.001)   # um, NA (proposed), rad, rad
 
 
@@ -619,9 +626,10 @@ def _autograd():
             return gout[:, None] * grad, None, None, None, None
 
     class Reconstruct(torch.autograd.Function):
-        """Tikhonov reconstruction f(d, theta) of a 3D model with theta (n, 4)
-        (float64, host) the optics' (defocus, na_det, tilt_zenith, tilt_azimuth);
-        forward: wo_transfer_function + wo_reconstruct at theta; backward:
+        """Tikhonov reconstruction f(d, theta) of a 3D model with theta (n, 4) or
+        (n, 6) (float64, host) the optics' leading PARAMS6 (defocus, na_det,
+        tilt_zenith, tilt_azimuth[, det_tilt, det_azimuth]); forward:
+        wo_transfer_function + wo_reconstruct at theta; backward:
         wo_reconstruct_grad (dL/dd and dL/dtheta, the bank recomputed)."""
 
         @staticmethod
@@ -630,10 +638,10 @@ def _autograd():
             opts = []
             for i, o in enumerate(optics):
                 oo = copy.copy(o)
-                for j, f in enumerate(PARAMS):
+                for j, f in enumerate(PARAMS6[: theta.shape[1]]):
                     setattr(oo, f, float(theta[i, j]))
                 opts.append(oo)
-            ctx.opts, ctx.eta, ctx.b = opts, eta, b
+            ctx.opts, ctx.eta, ctx.b, ctx.k = opts, eta, b, theta.shape[1]
             ctx.save_for_backward(d)
             tf = transfer_function(opts, device=d.device)
             return reconstruct(opts, tf, d, eta, b=b)
@@ -644,7 +652,7 @@ def _autograd():
             gth, gd = reconstruct_grad(ctx.opts, d, ctx.eta, g.contiguous(), b=ctx.b,
                                        want_theta=ctx.needs_input_grad[1],
                                        want_data=ctx.needs_input_grad[0])
-            return (gd, None if gth is None else torch.from_numpy(gth), None, None, None)
+            return (gd, None if gth is None else torch.from_numpy(gth[:, :ctx.k]), None, None, None)
 
     return LinearForward, MidbandLoss, Reconstruct
 

@@ -143,21 +143,34 @@ bool same_sampling(const wo_optics* a, const wo_optics* b) {
 int check_optics(const wo_optics* o) {
   if (!(o->na_det >= 0 && o->na_ill >= 0 && o->n_medium > 0 && o->edge_width >= 0))
     return WO_EINVAL;
-  if (!(isfinite(o->defocus) && isfinite(o->tilt_zenith) && isfinite(o->tilt_azimuth)))
+  if (!(isfinite(o->defocus) && isfinite(o->tilt_zenith) && isfinite(o->tilt_azimuth) &&
+        isfinite(o->det_tilt) && isfinite(o->det_azimuth)))
     return WO_EINVAL;
   const double km = o->n_medium / o->wavelength;
   const double dnu = fmin(1.0 / (o->nx * o->dx), 1.0 / (o->ny * o->dy));
   const double hw = o->edge_width * dnu;
-  if (o->na_det / o->wavelength + hw >= km) return WO_EINVAL;
+  // the detection pupil (the cap about a tilted detection axis) inside the shell
+  DevOptics dd;
+  memset(&dd, 0, sizeof(dd));
+  dd.wavelength = o->wavelength;
+  dd.na_det = o->na_det;
+  dd.n_medium = o->n_medium;
+  dd.det_tilt = o->det_tilt;
+  const double rdet = det_radius(dd);
+  if (rdet + hw >= km || fabs(o->det_tilt) + asin(fmin(o->na_det / o->n_medium, 1.0)) >= 0.5 * M_PI)
+    return WO_EINVAL;
+  if (o->det_tilt != 0.0)
+    for (int j = 0; j < 7; ++j)
+      if (o->zernike[j] != 0.0) return WO_EUNSUPPORTED;   // aberrations on a tilted pupil
   const double q0 = fabs(o->n_medium * sin(o->tilt_zenith) / o->wavelength);
   if (o->model != WO_MODEL_FLUOR_3D && o->na_ill / o->wavelength + q0 + hw >= km) return WO_EINVAL;
   const double nyq = fmin(0.5 / o->dx, 0.5 / o->dy);
   double lat, ax;
-  const double kd = fmin(o->na_det / o->wavelength + hw, km);
+  const double kd = fmin(rdet + hw, km);
   if (o->model == WO_MODEL_FLUOR_3D) {
-    lat = 2.0 * (o->na_det / o->wavelength + hw);
+    lat = 2.0 * (rdet + hw);
   } else {
-    lat = (o->na_det + o->na_ill) / o->wavelength + q0 + 2.0 * hw;
+    lat = rdet + o->na_ill / o->wavelength + q0 + 2.0 * hw;
   }
   ax = km - sqrt(km * km - kd * kd);
   if (lat >= nyq) return WO_EALIAS;
@@ -184,6 +197,10 @@ bool sectors_lit(const wo_optics& oo) {
   d.n_medium = oo.n_medium;
   d.tilt_zenith = oo.tilt_zenith;
   d.tilt_azimuth = oo.tilt_azimuth;
+  d.na_det = oo.na_det;
+  d.det_tilt = oo.det_tilt;
+  d.det_azimuth = oo.det_azimuth;
+  const DetAxis da = det_axis(d);
   double cy, cx;
   source_centre(d, &cy, &cx);
   const double dnu = fmin(1.0 / (oo.nx * oo.dx), 1.0 / (oo.ny * oo.dy));
@@ -192,7 +209,7 @@ bool sectors_lit(const wo_optics& oo) {
   for (int ky = 0; ky < oo.ny; ++ky)
     for (int kx = 0; kx < oo.nx; ++kx) {
       const double fy = fftfreq(ky, oo.ny, oo.dy), fx = fftfreq(kx, oo.nx, oo.dx);
-      const double P = disc(fy, fx, oo.na_det / oo.wavelength, hw);
+      const double P = det_pupil(d, da, fy, fx, hw);
       const double S = disc(fy - cy, fx - cx, oo.na_ill / oo.wavelength, hw);
       bg[octant(fy - cy, fx - cx)] += S * P * P;
     }
@@ -317,6 +334,8 @@ int field_sets(const wo_optics* o) { return o->model == WO_MODEL_SECTORS9_3D ? 9
 // twice P's support.  No wrap-around: the aliasing check keeps these sums
 // below Nyquist.  Each bound keeps one spare column or row; compact widths
 // are multiples of 16.
+DevOptics dev_optics(const wo_optics& o);
+
 LatSupport lateral_support(const wo_optics* o, int32_t n) {
   const Sampling sm = sampling_of(o);
   LatSupport ls = full_support(sm);
@@ -326,7 +345,7 @@ LatSupport lateral_support(const wo_optics* o, int32_t n) {
   int px = 0, py = 0, ax = 0, ay = 0;
   for (int i = 0; i < n; ++i) {
     const double hw = o[i].edge_width * dnu;
-    const double rd = o[i].na_det / o[i].wavelength + hw;
+    const double rd = det_radius(dev_optics(o[i])) + hw;   // the detection pupil's extent
     const double ri = o[i].na_ill / o[i].wavelength + hw;
     const double r = o[i].n_medium * sin(o[i].tilt_zenith) / o[i].wavelength;
     const double cy = fabs(r * sin(o[i].tilt_azimuth)), cx = fabs(r * cos(o[i].tilt_azimuth));
@@ -558,7 +577,7 @@ TuneLayout tune_layout(const wo_optics* o, int32_t n, int32_t starts) {
   L.off_dp = take((size_t)L.nv * L.dwpp * sizeof(double));
   const long gt = grad_tiles(sm);
   L.off_gp = take((size_t)L.nv * Z * gt * kGradAll * sizeof(double));
-  L.off_ip = take((size_t)L.nv * gt * 4 * sizeof(double));
+  L.off_ip = take((size_t)L.nv * gt * kThetaAll * sizeof(double));
   L.off_ropt = take((size_t)n * sizeof(DevOptics));
   L.off_reta = take((size_t)n * sizeof(float));
   L.total = b;
@@ -681,6 +700,8 @@ DevOptics dev_optics(const wo_optics& o) {
   d.tilt_azimuth = o.tilt_azimuth;
   d.edge_width = o.edge_width;
   for (int j = 0; j < 7; ++j) d.zern[j] = (float)o.zernike[j];
+  d.det_tilt = o.det_tilt;
+  d.det_azimuth = o.det_azimuth;
   return d;
 }
 
@@ -1462,7 +1483,7 @@ Grad3Layout grad3_layout(const wo_optics* o, int32_t n, const Shape& s, const La
   L.lp = take((size_t)n * loss_blocks(sm) * sizeof(double));
   L.dp = take((size_t)n * bwd_wg_per_patch(sm) * sizeof(double));
   L.gp = take((size_t)n * s.Z * grad_tiles(sm) * kGradAll * sizeof(double));
-  L.ip = take((size_t)n * grad_tiles(sm) * 4 * sizeof(double));
+  L.ip = take((size_t)n * grad_tiles(sm) * kThetaAll * sizeof(double));
   L.ab = take((size_t)n * 2 * s.Z * s.Y * sup.xc * sizeof(float2));
   L.bank = take((size_t)n * s.Z * 2 * plane * sizeof(float2));
   L.D = take((size_t)n * s.C * s.Z * plane * sizeof(float2));
@@ -1529,6 +1550,7 @@ extern "C" int wo_reconstruct_grad(const wo_optics* o, int32_t n, const float* d
   }
   Sampling sm = sampling_of(o);
   for (int i = 0; i < n; ++i) sm.aberrated |= aberrated(o[i]) ? 1 : 0;
+  sm.det_grad = 1;   // also d/d(det_tilt, det_azimuth)
   const long Z = s.Z, Y = s.Y, X = s.X, Xh = s.Xh, plane = Y * Xh;
   const int C = s.C, P = s.P;
   const double nfull = (double)Z * Y * X;
@@ -1567,7 +1589,7 @@ extern "C" int wo_reconstruct_grad(const wo_optics* o, int32_t n, const float* d
     WO_TRY(hipMemcpyAsync(t.data(), tst, n * sizeof(TuneState), hipMemcpyDeviceToHost, hs));
     WO_TRY(hipStreamSynchronize(hs));
     for (int i = 0; i < n; ++i)
-      for (int j = 0; j < 4; ++j) dL_dtheta_out[4 * i + j] = t[i].grad[j];
+      for (int j = 0; j < kThetaAll; ++j) dL_dtheta_out[kThetaAll * i + j] = t[i].grad[j];
   }
   return WO_OK;
 }
@@ -1673,8 +1695,8 @@ static int midband(const wo_optics* o, int32_t n, const float* d, const double* 
       const int i = g.idx[j];
       loss_out[i] = h[j].loss;
       if (grad_out && with_aberration) {
-        for (int k = 0; k < 4; ++k) grad_out[kGradAll * i + k] = h[j].grad[k];
-        for (int k = 0; k < 7; ++k) grad_out[kGradAll * i + 4 + k] = h[j].gab[k];
+        for (int k = 0; k < 4; ++k) grad_out[11 * i + k] = h[j].grad[k];
+        for (int k = 0; k < 7; ++k) grad_out[11 * i + 4 + k] = h[j].gab[k];
       } else if (grad_out) {
         for (int k = 0; k < 4; ++k) grad_out[4 * i + k] = h[j].grad[k];
       }

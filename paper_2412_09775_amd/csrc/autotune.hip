@@ -413,9 +413,11 @@ hipError_t launch_tf_rows_bwd(const double* partials, const Sampling& sm, int nv
 // Inverse Y transform of u_A, u_B columns, then per lateral frequency the
 // contraction 4 Re(U_B dB/dtheta + U_A dA/dtheta).  A workgroup owns one column
 // tile and a chunk of ZC planes; the pupils and their derivatives, which do not
-// depend on z, are evaluated once.  gpart[((v*nzc + chunk)*tiles + tile)*4 + j];
-// the first chunk also writes dI_bg/dtheta partials to ipart[(v*tiles + tile)*4 + j].
-template <int NS, bool AB>
+// depend on z, are evaluated once.  gpart[((v*nzc + chunk)*tiles + tile)*KG + j]
+// with KG = TH (+ 7 aberration coefficients when AB), TH = 4 theta components
+// (+ det_tilt, det_azimuth when DT); the first chunk also writes dI_bg/dtheta
+// partials to ipart[(v*tiles + tile)*TH + j].
+template <int NS, bool AB, bool DT>
 __global__ __launch_bounds__(1024) void k_tf_grad_y(const DevOptics* __restrict__ opt, Sampling sm,
                                                     const float2* __restrict__ ab,
                                                     double* __restrict__ gpart,
@@ -441,8 +443,12 @@ __global__ __launch_bounds__(1024) void k_tf_grad_y(const DevOptics* __restrict_
   const int wsh = pow2_shift(W);     // W is a power of two
   // per element: phase rate 2 kz (FP64, the phase needs it) and the pupil
   // products of the contraction (FP32)
+  constexpr int TH = DT ? kThetaAll : 4;
   double tkz[EPT];
   float SP[EPT], gkP[EPT], SdP[EPT], gkdP[EPT], dSzP[EPT], dSaP[EPT];
+  // with DT: the detection pupil's derivatives along the tilt and azimuth of its
+  // axis, in the same products as dP/dNA
+  float SdPt[DT ? EPT : 1], gkdPt[DT ? EPT : 1], SdPa[DT ? EPT : 1], gkdPa[DT ? EPT : 1];
   // aberration-aware (AB): the aberration phase 2 W in units of pi, and
   // Q = sum_z (S P Im(U_A e) + gk P Re(U_B e)), which every derivative of the
   // aberration phase multiplies (d/dc_j: -2 pi Z_j; the NA term: -2 pi dW/dNA)
@@ -451,17 +457,19 @@ __global__ __launch_bounds__(1024) void k_tf_grad_y(const DevOptics* __restrict_
   {
     const double hw = soft_halfwidth(o, sm);
     const double km = o.n_medium / o.wavelength;
-    const double rd = o.na_det / o.wavelength, ri = o.na_ill / o.wavelength;
+    const double ri = o.na_ill / o.wavelength;
+    const DetAxis dax = det_axis(o);
     double cy, cx;
     source_centre(o, &cy, &cx);
     const double rq0 = o.n_medium * sin(o.tilt_zenith) / o.wavelength;
     const double drq0 = o.n_medium * cos(o.tilt_zenith) / o.wavelength;
     const double sa = sin(o.tilt_azimuth), ca = cos(o.tilt_azimuth);
-    double di[4] = {0.0, 0.0, 0.0, 0.0};
+    double di[kThetaAll] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int i = 0; i < EPT; ++i) {
       tkz[i] = 0.0;
       SP[i] = gkP[i] = SdP[i] = gkdP[i] = dSzP[i] = dSaP[i] = 0.f;
+      if constexpr (DT) SdPt[i] = gkdPt[i] = SdPa[i] = gkdPa[i] = 0.f;
       if constexpr (AB) {
         ab2[i] = 0.f;
         Qe[i] = 0.0;
@@ -474,8 +482,9 @@ __global__ __launch_bounds__(1024) void k_tf_grad_y(const DevOptics* __restrict_
       const int kx = field_column(c, KP, X, XC);
       const double fy = fftfreq(ky, Y, sm.dy), fx = fftfreq(kx, X, sm.dx);
       const double rp = sqrt(fy * fy + fx * fx);
-      const double P = disc(fy, fx, rd, hw);
-      const double dP = edge_slope(rd - rp, hw) / o.wavelength;     // dP / dNA_det
+      const double P = det_pupil(o, dax, fy, fx, hw);
+      double dP, dPt, dPa;                                           // dP / d(NA_det, tilt, azimuth)
+      det_pupil_derivs(o, dax, fy, fx, hw, &dP, &dPt, &dPa);
       const double qy = fy - cy, qx = fx - cx;
       const double rq = sqrt(qy * qy + qx * qx);
       const double S = disc(qy, qx, ri, hw);
@@ -487,7 +496,11 @@ __global__ __launch_bounds__(1024) void k_tf_grad_y(const DevOptics* __restrict_
       di[1] += 2.0 * S * P * dP;
       di[2] += dSz * P * P;
       di[3] += dSa * P * P;
-      if (P == 0.0 && dP == 0.0) continue;
+      if constexpr (DT) {
+        di[4] += 2.0 * S * P * dPt;
+        di[5] += 2.0 * S * P * dPa;
+      }
+      if (P == 0.0 && dP == 0.0 && (!DT || (dPt == 0.0 && dPa == 0.0))) continue;
       const double kz = sqrt(fmax(km * km - rp * rp, 0.0));
       const double gk = kz > 0.0 ? km / kz : 0.0;
       tkz[i] = 2.0 * kz;
@@ -499,16 +512,22 @@ __global__ __launch_bounds__(1024) void k_tf_grad_y(const DevOptics* __restrict_
       gkdP[i] = (float)(gk * dP);
       dSzP[i] = (float)(dSz * P);
       dSaP[i] = (float)(dSa * P);
+      if constexpr (DT) {
+        SdPt[i] = (float)(S * dPt);
+        gkdPt[i] = (float)(gk * dPt);
+        SdPa[i] = (float)(S * dPa);
+        gkdPa[i] = (float)(gk * dPa);
+      }
     }
     if (zc == 0) {
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
+      for (int j = 0; j < TH; ++j) {
         const double t = block_sum_d(di[j], red);
-        if (tid == 0) ipart[(v * tiles_x + tile) * 4 + j] = t;
+        if (tid == 0) ipart[(v * tiles_x + tile) * TH + j] = t;
       }
     }
   }
-  double g[4] = {0.0, 0.0, 0.0, 0.0};
+  double g[kThetaAll] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   const int zend = min(Z, (zc + 1) * ZC);
   // the tile of plane z: element e = (ky, field, w) from ab; plane z + 1 is loaded
   // into registers while plane z is transformed and contracted
@@ -543,7 +562,8 @@ __global__ __launch_bounds__(1024) void k_tf_grad_y(const DevOptics* __restrict_
     for (int i = 0; i < EPT; ++i) {
       const int e = tid + i * nthr;
       if (e >= Y * W || (tkz[i] == 0.0 && SP[i] == 0.f && SdP[i] == 0.f && gkdP[i] == 0.f &&
-                         dSzP[i] == 0.f && dSaP[i] == 0.f))
+                         dSzP[i] == 0.f && dSaP[i] == 0.f &&
+                         (!DT || (SdPt[i] == 0.f && gkdPt[i] == 0.f && SdPa[i] == 0.f && gkdPa[i] == 0.f))))
         continue;
       const int ky = e >> wsh, w = e & (W - 1);
       double arg = tkz[i] * dzr;
@@ -566,10 +586,15 @@ __global__ __launch_bounds__(1024) void k_tf_grad_y(const DevOptics* __restrict_
       g[1] += (double)(SdP[i] * ua_re - gkdP[i] * ub_im);
       g[2] += (double)(dSzP[i] * ua_re);
       g[3] += (double)(dSaP[i] * ua_re);
+      if constexpr (DT) {
+        // the detection axis moves P as NA does: S dP e in A, i gk dP e in B
+        g[4] += (double)(SdPt[i] * ua_re - gkdPt[i] * ub_im);
+        g[5] += (double)(SdPa[i] * ua_re - gkdPa[i] * ub_im);
+      }
     }
     __syncthreads();
   }
-  constexpr int KG = AB ? kGradAll : 4;
+  constexpr int KG = TH + (AB ? 7 : 0);
   double ga[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   if constexpr (AB) {
     const double tp = 2.0 * M_PI;
@@ -587,7 +612,7 @@ __global__ __launch_bounds__(1024) void k_tf_grad_y(const DevOptics* __restrict_
   }
 #pragma unroll
   for (int j = 0; j < KG; ++j) {
-    const double t = block_sum_d(4.0 * (j < 4 ? g[j] : ga[j - 4]), red);
+    const double t = block_sum_d(4.0 * (j < TH ? g[j] : ga[j - TH]), red);
     if (tid == 0) gpart[((v * nzc + zc) * tiles_x + tile) * KG + j] = t;
   }
 }
@@ -639,8 +664,14 @@ hipError_t launch_tf_grad_y(const DevOptics* opt, const Sampling& sm, int nv, co
   const size_t lds = (size_t)(sm.ny + sm.ny * 2 * W) * sizeof(float2);
   ScopedTiming _t("k_tf_grad_y", s);
 #define WO_GRAD(NN, AA)                                                                          \
-  hipLaunchKernelGGL((k_tf_grad_y<NN, AA>), dim3((unsigned)nwg), dim3(thr), lds, s, opt, sm, ab, gpart, \
-                     ipart, W, tiles, ZC, ls.xc, ls.kp, plan)
+  do {                                                                                           \
+    if (sm.det_grad)                                                                             \
+      hipLaunchKernelGGL((k_tf_grad_y<NN, AA, true>), dim3((unsigned)nwg), dim3(thr), lds, s, opt, sm, ab, \
+                         gpart, ipart, W, tiles, ZC, ls.xc, ls.kp, plan);                        \
+    else                                                                                         \
+      hipLaunchKernelGGL((k_tf_grad_y<NN, AA, false>), dim3((unsigned)nwg), dim3(thr), lds, s, opt, sm, ab, \
+                         gpart, ipart, W, tiles, ZC, ls.xc, ls.kp, plan);                        \
+  } while (0)
 #define X_(NN)                                                                                   \
   case NN:                                                                                       \
     if (sm.aberrated) WO_GRAD(NN, true); else WO_GRAD(NN, false);                                \
@@ -681,28 +712,29 @@ __global__ __launch_bounds__(256) void k_adam(DevOptics* __restrict__ opt,
   acc = 0.0;
   for (long i = tid; i < tiles_x; i += blockDim.x) acc += ppart[v * tiles_x + i];
   const double ibg = block_sum_d(acc, red);
-  const int KG = sm.aberrated ? kGradAll : 4;
-  double gj[kGradAll], dij[4];
+  const int TH = sm.det_grad ? kThetaAll : 4;
+  const int KG = TH + (sm.aberrated ? 7 : 0);
+  double gj[kGradAll], dij[kThetaAll];
   for (int j = 0; j < KG; ++j) {
     acc = 0.0;
     for (long i = tid; i < gn; i += blockDim.x) acc += gpart[(v * gn + i) * KG + j];
     gj[j] = block_sum_d(acc, red);
   }
-  for (int j = 0; j < 4; ++j) {
+  for (int j = 0; j < TH; ++j) {
     acc = 0.0;
-    for (long i = tid; i < gtiles; i += blockDim.x) acc += ipart[(v * gtiles + i) * 4 + j];
+    for (long i = tid; i < gtiles; i += blockDim.x) acc += ipart[(v * gtiles + i) * TH + j];
     dij[j] = block_sum_d(acc, red);
   }
   if (tid != 0) return;
   TuneState s = st[v];
   const double N = (double)sm.ny * sm.nx;
   const double loss = -lsum / s.band_count;
-  double grad[4];
-  for (int j = 0; j < 4; ++j) grad[j] = gj[j] - 4.0 * dsum / (N * ibg * ibg) * dij[j];
+  double grad[kThetaAll] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int j = 0; j < TH; ++j) grad[j] = gj[j] - 4.0 * dsum / (N * ibg * ibg) * dij[j];
   s.loss = loss;
-  for (int j = 0; j < 4; ++j) s.grad[j] = grad[j];
+  for (int j = 0; j < kThetaAll; ++j) s.grad[j] = grad[j];
   // I_bg = sum S |P|^2 does not depend on the aberration
-  for (int j = 0; j < 7; ++j) s.gab[j] = KG > 4 ? gj[4 + j] : 0.0;
+  for (int j = 0; j < 7; ++j) s.gab[j] = KG > TH ? gj[TH + j] : 0.0;
   if (update) {
     DevOptics o = opt[v];
     double th[4] = {o.defocus, o.na_det, o.tilt_zenith, o.tilt_azimuth};

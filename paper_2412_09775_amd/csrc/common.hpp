@@ -450,6 +450,7 @@ struct DevOptics {
   double ibg;
   int sector;              // illumination aperture: -1 the full disc, 0..7 an azimuthal sector
   float zern[7];           // detection aberration, waves, Noll j = 5..11
+  double det_tilt, det_azimuth;   // oblique detection: zenith and azimuth of the detection axis
 };
 
 // Polarisation coupling kappa_cp of one patch in FP32, (re, im) per channel c
@@ -587,7 +588,7 @@ struct TuneState {
   double m[4], v[4];
   double lr[4], lo[4], hi[4];
   double eta, nu_c, band_count;
-  double loss, grad[4];
+  double loss, grad[6];    // defocus, na_det, tilt_zenith, tilt_azimuth, det_tilt, det_azimuth
   double gab[7];   // dL / d zernike[j] (filled when the gradient is aberration-aware)
   // Adam on the aberration coefficients (mask bits 4..10): moments, one rate
   // and the box [-bound, bound] shared by the seven
@@ -598,7 +599,10 @@ struct TuneState {
 
 // Gradient components per partial: theta (4), then the 7 aberration coefficients
 // when the gradient kernels run aberration-aware.
-constexpr int kGradAll = 11;
+constexpr int kGradAll = 13;
+// Parameter gradient components before the aberration coefficients: theta
+// (4), then the detection axis (2) when the gradient kernels compute them.
+constexpr int kThetaAll = 6;
 
 // Sampling shared by every patch of a call.
 struct Sampling {
@@ -606,6 +610,7 @@ struct Sampling {
   int nz, ny, nx;
   double dz, dy, dx;
   int aberrated = 0;   // some patch has detection aberrations (selects the kernel variant)
+  int det_grad = 0;    // the gradient kernels also form d/d(det_tilt, det_azimuth)
 };
 
 __host__ __device__ __forceinline__ double fftfreq(int k, int n, double d) {
@@ -653,6 +658,68 @@ __host__ __device__ __forceinline__ double disc(double fy, double fx, double rad
   const double r2 = fy * fy + fx * fx;
   if (hw == 0.0) return r2 <= radius * radius ? 1.0 : 0.0;
   return edge_profile(radius - sqrt(r2), hw);
+}
+
+// Detection pupil (Ext. Data Fig. 3b, calc_det_pupil): the disc of radius
+// NA_det / lambda0 or, with oblique detection, the cap of the shell within that
+// NA about the detection axis a tilted by det_tilt in the azimuth det_azimuth,
+// a = (sin t sin az, sin t cos az, cos t) in (y, x, z): P = edge(NA_det/lambda0 - |p'|)
+// with |p'|^2 = k_m^2 - (k . a)^2 the lateral distance in the tilted frame,
+// k = (p, kz(p)), and k . a > 0.
+struct DetAxis {
+  double ay, ax, az;
+};
+__host__ __device__ __forceinline__ DetAxis det_axis(const DevOptics& o) {
+  const double st = sin(o.det_tilt);
+  return DetAxis{st * sin(o.det_azimuth), st * cos(o.det_azimuth), cos(o.det_tilt)};
+}
+
+__host__ __device__ __forceinline__ double det_pupil(const DevOptics& o, const DetAxis& a, double fy,
+                                                     double fx, double hw) {
+  const double rd = o.na_det / o.wavelength;
+  if (o.det_tilt == 0.0) return disc(fy, fx, rd, hw);
+  const double km = o.n_medium / o.wavelength;
+  const double p2 = fy * fy + fx * fx;
+  if (!(p2 < km * km)) return 0.0;
+  const double kz = sqrt(km * km - p2);
+  const double ka = fy * a.ay + fx * a.ax + kz * a.az;
+  if (!(ka > 0.0)) return 0.0;
+  const double pp2 = km * km - ka * ka;
+  if (hw == 0.0) return pp2 <= rd * rd ? 1.0 : 0.0;
+  return edge_profile(rd - sqrt(fmax(pp2, 0.0)), hw);
+}
+
+// Partial derivatives of det_pupil with respect to NA_det, det_tilt and
+// det_azimuth: P = edge(rd - |p'|), d|p'| = -(k . a)(k . da) / |p'| (all zero
+// for the hard edge).
+__device__ __forceinline__ void det_pupil_derivs(const DevOptics& o, const DetAxis& a, double fy,
+                                                 double fx, double hw, double* dna, double* dt,
+                                                 double* daz) {
+  *dna = *dt = *daz = 0.0;
+  const double km = o.n_medium / o.wavelength;
+  const double p2 = fy * fy + fx * fx;
+  if (!(p2 < km * km) || hw == 0.0) return;
+  const double kz = sqrt(km * km - p2);
+  const double ka = fy * a.ay + fx * a.ax + kz * a.az;
+  if (!(ka > 0.0)) return;
+  const double pp = sqrt(fmax(km * km - ka * ka, 0.0));
+  const double sl = edge_slope(o.na_det / o.wavelength - pp, hw);
+  *dna = sl / o.wavelength;
+  if (sl == 0.0 || !(pp > 0.0)) return;
+  const double ct = cos(o.det_tilt), st = sin(o.det_tilt);
+  const double ca = cos(o.det_azimuth), sa = sin(o.det_azimuth);
+  const double kdt = fy * ct * sa + fx * ct * ca - kz * st;   // k . da/dt
+  const double kda = fy * st * ca - fx * st * sa;             // k . da/daz
+  *dt = sl * ka * kdt / pp;
+  *daz = sl * ka * kda / pp;
+}
+
+// Radius about p = 0 of a disc holding the detection pupil (without its soft
+// edge): NA_det / lambda0, or k_m sin(det_tilt + asin(NA_det / n)).
+__host__ __device__ __forceinline__ double det_radius(const DevOptics& o) {
+  if (o.det_tilt == 0.0) return o.na_det / o.wavelength;
+  const double a = fabs(o.det_tilt) + asin(fmin(o.na_det / o.n_medium, 1.0));
+  return (o.n_medium / o.wavelength) * (a < 0.5 * M_PI ? sin(a) : 1.0);
 }
 
 __device__ __forceinline__ double soft_halfwidth(const DevOptics& o, const Sampling& sm) {

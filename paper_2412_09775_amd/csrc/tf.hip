@@ -169,7 +169,8 @@ __global__ __launch_bounds__(1024) void k_tf_fields_y(const DevOptics* __restric
     {
       const double hw = soft_halfwidth(o, sm);
       const double km = o.n_medium / o.wavelength;
-      const double rd = o.na_det / o.wavelength, ri = o.na_ill / o.wavelength;
+      const double ri = o.na_ill / o.wavelength;
+      const DetAxis dax = det_axis(o);
       double cy, cx;
       source_centre(o, &cy, &cx);
       double psum = 0.0;
@@ -187,7 +188,7 @@ __global__ __launch_bounds__(1024) void k_tf_fields_y(const DevOptics* __restric
           if (j < nl * NB0 && c < XC) {
             const int ky = k + r * NB0;
             const double fy = freq_y(ky), fx = fftfreq(kx, X, sm.dx);
-            const double P = disc(fy, fx, rd, hw);
+            const double P = det_pupil(o, dax, fy, fx, hw);
             if (P != 0.0) {
               const double kz = sqrt(fmax(km * km - (fy * fy + fx * fx), 0.0));
               tkz[b][r] = 2.0 * kz;
@@ -280,7 +281,8 @@ __global__ __launch_bounds__(1024) void k_tf_fields_y(const DevOptics* __restric
     {
       const double hw = soft_halfwidth(o, sm);
       const double km = o.n_medium / o.wavelength;
-      const double rd = o.na_det / o.wavelength, ri = o.na_ill / o.wavelength;
+      const double ri = o.na_ill / o.wavelength;
+      const DetAxis dax = det_axis(o);
       double cy, cx;
       source_centre(o, &cy, &cx);
       double psum = 0.0;
@@ -297,7 +299,7 @@ __global__ __launch_bounds__(1024) void k_tf_fields_y(const DevOptics* __restric
           const int kx = field_column(c, KP, X, XC);
           if (c < XC) {
             const double fy = freq_y(ky), fx = fftfreq(kx, X, sm.dx);
-            const double P = disc(fy, fx, rd, hw);
+            const double P = det_pupil(o, dax, fy, fx, hw);
             if (P != 0.0) {
               const double kz = sqrt(fmax(km * km - (fy * fy + fx * fx), 0.0));
               tkz[i] = 2.0 * kz;
@@ -377,14 +379,17 @@ bool tf_fields_choice_ok(int Z, const FftChoice& c) {
   return c.w >= 1 && c.w <= Z && c.threads == 0 && c.plan == 0;
 }
 
-// About 256 workgroups: each evaluates the z-independent pupil factors of its
-// tile once (FP64 square roots and divisions) and reuses them for up to 16
-// planes (96x512x512, 60 tiles: 93 us with 2 planes per workgroup, 70 us
-// with 16); the tuner picks the chunk by timing (12 planes: 58 us there).
+// About 480 workgroups: each evaluates the z-independent pupil factors of its
+// tile once (FP64 square roots and divisions) and reuses them for its planes.
+// Few planes per workgroup repeat that set-up, many leave too few waves to hide
+// the passes' waits: measured over 1..64 planes, 12 is best on 96x512x512 (60
+// tiles: 1 plane 117 us, 12 planes 53 us, 16 planes 65 us, 64 planes 148 us)
+// and on 64x1024x1024 (76 tiles: 1 plane 106 us, 12 planes 58 us, 64 planes
+// 154 us); the tuner picks the chunk by timing.
 FftChoice tf_fields_default(int Z, long tiles, long npatch) {
   Sampling sm{};
   sm.nz = Z;
-  return FftChoice{tf_z_chunk(sm, tiles, npatch, 256), 0, 0};
+  return FftChoice{tf_z_chunk(sm, tiles, npatch, 480), 0, 0};
 }
 
 // Column-tile width of the field kernel: at most 4096 elements (512 threads)

@@ -117,6 +117,16 @@ CASES = {
     "pol5_band": [pol5(nz=16, ny=96, nx=128, tilt_zenith=0.2, tilt_azimuth=0.6, edge_width=0.5)],
     "pol5_band_batch2_swings": [pol5(nz=12, ny=96, nx=96, swing=0.1),
                                 pol5(nz=12, ny=96, nx=96, swing=0.05, defocus=0.3, na_ill=0.3)],
+    # oblique detection: the detection pupil is the cap about a tilted axis (every
+    # model; soft and hard edges; a batch with tilted and straight detection)
+    "labelfree_3d_oblique": [labelfree(nz=16, ny=96, nx=80, na_det=0.9, det_tilt=0.35, det_azimuth=0.6,
+                                       defocus=0.2, edge_width=0.5)],
+    "labelfree_3d_oblique_hard_batch2": [labelfree(nz=12, ny=64, nx=64, na_det=0.8, det_tilt=0.3,
+                                                   det_azimuth=-1.0),
+                                         labelfree(nz=12, ny=64, nx=64, na_det=0.8)],
+    "fluor_oblique": [fluor(nz=24, ny=64, nx=64, na_det=0.8, det_tilt=0.4, det_azimuth=2.0, edge_width=0.5)],
+    "pol5_oblique": [pol5(nz=12, ny=96, nx=96, det_tilt=0.3, det_azimuth=0.4, edge_width=0.5)],
+    "thin_oblique": [thin(nz=16, ny=64, nx=64, na_det=0.9, det_tilt=0.3, det_azimuth=1.2)],
 }
 
 
