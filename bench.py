@@ -827,6 +827,23 @@ def autotune_section(api, torch, dev, n, iters, net, cnn_iters):
     return res
 
 
+CNN_CHANNELS = (1, 32, 64, 128, 256)
+BF16_PEAK_TFLOPS = 2500.0     # MI355X dense BF16 MFMA
+
+
+def cnn_flops_per_sample(shape=(32, 64, 64)):
+    """Convolution FLOPs of one training sample (forward, weight gradient, and the
+    input gradient of every block but the first): 2 * positions * Cout * 27 * Cin
+    per GEMM; stride 2, padding 1."""
+    d, h, w = shape
+    total = 0
+    for l in range(len(CNN_CHANNELS) - 1):
+        d, h, w = (d - 1) // 2 + 1, (h - 1) // 2 + 1, (w - 1) // 2 + 1
+        g = 2 * d * h * w * CNN_CHANNELS[l + 1] * 27 * CNN_CHANNELS[l]
+        total += g * (2 if l == 0 else 3)
+    return total
+
+
 def train_cnn(api, torch, dev, patches, epochs):
     """The learned initialiser trained on forward-model patches 32x64x64 (not part of
     any patches/s figure); a quarter of the patches keep only their central 16 planes
@@ -846,8 +863,15 @@ def train_cnn(api, torch, dev, patches, epochs):
     del stacks
     print(f"[bench] cnn trained: {patches} patches x {epochs} epochs in {t_train:.1f}s, "
           f"loss {hist[0]:.3f} -> {hist[-1]:.3f}", file=sys.stderr, flush=True)
+    flops = cnn_flops_per_sample() * patches * epochs
+    achieved = flops / t_train * 1e-12
     return net, {"patches": patches, "epochs": epochs, "batch": 64, "simulate_s": round(t_sim, 2),
-                 "train_s": round(t_train, 2), "loss_first_last": [round(hist[0], 4), round(hist[-1], 4)]}
+                 "train_s": round(t_train, 2), "loss_first_last": [round(hist[0], 4), round(hist[-1], 4)],
+                 "roofline": {"bound": "mfma", "achieved": round(achieved, 2), "peak": BF16_PEAK_TFLOPS,
+                              "unit": "TFLOP/s", "frac": round(achieved / BF16_PEAK_TFLOPS, 4),
+                              "flops_per_sample": cnn_flops_per_sample(),
+                              "note": "convolution FLOPs over the whole training time (AdamW, head, "
+                                      "normalisation and GELU backward included in the time)"}}
 
 
 RESTORE_Z = (16, 24, 32, 48, 64)

@@ -467,7 +467,8 @@ int wo_fft_candidates(const char* key_line, char* buf, size_t len, size_t* neede
  * Parameter layout (flat FP32): for each block, weights [Cout][3][3][3][Cin]
  * then bias [Cout]; then head weights [3][256] and bias [3].
  * Inputs x: device [batch][nz][ny][nx] FP32 stacks; each sample is scaled by
- * its RMS before the first convolution. */
+ * its RMS before the first convolution.  batch * nz * ny * nx must stay below
+ * 2^31 (else WO_EINVAL, and a workspace size of 0). */
 int64_t wo_cnn_param_count(void);
 size_t wo_cnn_workspace_size(int32_t batch, int32_t nz, int32_t ny, int32_t nx);
 /* y_out: device [batch][3]. */
@@ -488,7 +489,8 @@ int wo_cnn_train_step(float* params, float* adam_m, float* adam_v, int32_t t, do
  * 16-bit storage), channels-last x [N][D][H][W][Cin], weights [Cout][27][Cin]:
  * forward out [N][Do][Ho][Wo][Cout] (no bias), input gradient from
  * gz [N][Do][Ho][Wo][Cout] to out [N][D][H][W][Cin], weight gradient
- * out [Cout][27][Cin] (ws: FP32 split-K partials).  Do = (D - 1)/2 + 1. */
+ * out [Cout][27][Cin] (ws: FP32 split-K partials).  Do = (D - 1)/2 + 1;
+ * N * D * H * W below 2^31 (else WO_EINVAL). */
 int wo_conv3d_forward(const uint16_t* x, const uint16_t* w, int32_t N, int32_t D, int32_t H,
                       int32_t W, int32_t Cin, int32_t Cout, float* out, void* stream);
 int wo_conv3d_input_grad(const uint16_t* gz, const uint16_t* w, int32_t N, int32_t D, int32_t H,

@@ -117,6 +117,13 @@ def load(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise RuntimeError(f"{path} is missing: build it with paper_2412_09775_amd.build.build()")
+    # torch ships its own HIP runtime: load it first so that the library binds to
+    # the same one and torch's device memory and streams are valid in its calls
+    # (a library loaded first would pull in the system runtime beside torch's)
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(path)
     vp, sz, i32 = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int32
     op = ctypes.POINTER(WoOptics)

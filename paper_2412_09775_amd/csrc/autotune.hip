@@ -78,7 +78,7 @@ __global__ __launch_bounds__(256) void k_loss_grad(const DevOptics* __restrict__
     }
     const float a00 = m00 + eta, a11 = m11 + eta;
     const float det = a00 * a11 - (m10.x * m10.x + m10.y * m10.y);
-    const float idet = 1.f / det;
+    const float idet = __builtin_amdgcn_rcpf(det);   // hardware reciprocal (about 1 ulp)
     // F = M^-1 r with M = [[a00, conj(m10)], [m10, a11]]
     const float2 F0 = cscale(csub(cscale(r0, a11), cmul(cconj(m10), r1)), idet);
     const float2 F1 = cscale(csub(cscale(r1, a00), cmul(m10, r0)), idet);

@@ -55,14 +55,20 @@ struct TapCh {  // (tap, channel) of a K index, advanced incrementally
 struct GatherIm2col {
   const u16* x;
   ConvGeom g;
-  struct Row { long n; int d0, h0, w0; };
+  // positions (batch included) stay below 2^31 (checked on the host): 32-bit
+  // index arithmetic, one widening multiply per address
+  struct Row { int n, d0, h0, w0; };
   __device__ __forceinline__ Row row(long m) const {
     Row r;
-    long q = m;
-    const int ow = (int)(q % g.Wo); q /= g.Wo;
-    const int oh = (int)(q % g.Ho); q /= g.Ho;
-    const int od = (int)(q % g.Do);
-    r.n = q / g.Do;
+    unsigned q = (unsigned)m;
+    const unsigned wo = (unsigned)g.Wo, ho = (unsigned)g.Ho, dd = (unsigned)g.Do;
+    unsigned q1 = q / wo;
+    const int ow = (int)(q - q1 * wo);
+    unsigned q2 = q1 / ho;
+    const int oh = (int)(q1 - q2 * ho);
+    const unsigned q3 = q2 / dd;
+    const int od = (int)(q2 - q3 * dd);
+    r.n = (int)q3;
     r.d0 = 2 * od - 1; r.h0 = 2 * oh - 1; r.w0 = 2 * ow - 1;
     return r;
   }
@@ -71,7 +77,8 @@ struct GatherIm2col {
     const int kw = t.tap % 3, kh = (t.tap / 3) % 3, kd = t.tap / 9;
     const int id = r.d0 + kd, ih = r.h0 + kh, iw = r.w0 + kw;
     if (id < 0 || id >= g.D || ih < 0 || ih >= g.H || iw < 0 || iw >= g.W) return nullptr;
-    return x + (((r.n * g.D + id) * g.H + ih) * g.W + iw) * g.C + t.ch;
+    const unsigned pos = (((unsigned)r.n * g.D + id) * g.H + ih) * g.W + iw;
+    return x + (long)((unsigned long)pos * (unsigned)g.C) + t.ch;
   }
   __device__ __forceinline__ u16 at(const Row& r, TapCh t) const {
     const u16* p = ptr(r, t);
@@ -112,14 +119,17 @@ struct GatherCol2imClass {
   int pd, ph, pw; // parity of the class
   int cd, ch, cw; // class extents: positions with that parity
   int nd, nh, nw; // valid taps per axis (1 or 2)
-  struct Row { long n; int d, h, w; };
+  struct Row { int n, d, h, w; };   // 32-bit, as in GatherIm2col
   __device__ __forceinline__ Row row(long m) const {
     Row r;
-    long q = m;
-    const int iw = (int)(q % cw); q /= cw;
-    const int ih = (int)(q % ch); q /= ch;
-    const int id = (int)(q % cd);
-    r.n = q / cd;
+    const unsigned q = (unsigned)m;
+    const unsigned q1 = q / (unsigned)cw;
+    const int iw = (int)(q - q1 * (unsigned)cw);
+    const unsigned q2 = q1 / (unsigned)ch;
+    const int ih = (int)(q1 - q2 * (unsigned)ch);
+    const unsigned q3 = q2 / (unsigned)cd;
+    const int id = (int)(q2 - q3 * (unsigned)cd);
+    r.n = (int)q3;
     r.d = 2 * id + pd; r.h = 2 * ih + ph; r.w = 2 * iw + pw;
     return r;
   }
@@ -131,7 +141,8 @@ struct GatherCol2imClass {
     if (od2 < 0 || oh2 < 0 || ow2 < 0) return nullptr;
     const int od = od2 >> 1, oh = oh2 >> 1, ow = ow2 >> 1;
     if (od >= g.Do || oh >= g.Ho || ow >= g.Wo) return nullptr;
-    return gz + (((r.n * g.Do + od) * g.Ho + oh) * g.Wo + ow) * g.C + t.ch;
+    const unsigned pos = (((unsigned)r.n * g.Do + od) * g.Ho + oh) * g.Wo + ow;
+    return gz + (long)((unsigned long)pos * (unsigned)g.C) + t.ch;
   }
   __device__ __forceinline__ u16 at(const Row& r, TapCh t) const {
     const u16* p = ptr(r, t);
@@ -146,7 +157,7 @@ struct GatherCol2imClass {
   // the global input position of class row m (output row mapping)
   __device__ __forceinline__ long out_row(long m) const {
     const Row r = row(m);
-    return ((r.n * g.D + r.d) * g.H + r.h) * g.W + r.w;
+    return (long)((((unsigned)r.n * g.D + r.d) * g.H + r.h) * g.W + r.w);
   }
 };
 
@@ -162,7 +173,7 @@ struct GatherWTClass {
     const int jw = t.tap % nw, jh = (t.tap / nw) % nh, jd = t.tap / (nw * nh);
     const int kd = nd == 1 ? 1 : 2 * jd, kh = nh == 1 ? 1 : 2 * jh, kw = nw == 1 ? 1 : 2 * jw;
     const int tap = (kd * 3 + kh) * 3 + kw;
-    return ((long)t.ch * 27 + tap) * Cin;
+    return (long)((t.ch * 27 + tap) * Cin);
   }
   __device__ __forceinline__ u16 at(const Row& r, TapCh t) const { return w[off(t) + r.ci]; }
   // 8 consecutive rows (ci .. ci + 7) at one k, when Cin % 8 == 0
@@ -181,11 +192,12 @@ struct GatherT {
   struct Row { int co; };
   __device__ __forceinline__ Row row(long m) const { return Row{(int)m}; }
   __device__ __forceinline__ int chans() const { return 1; }
-  __device__ __forceinline__ u16 at(const Row& r, TapCh t) const { return gz[(long)t.tap * Cout + r.co]; }
+  __device__ __forceinline__ long off(TapCh t) const { return (long)((unsigned long)(unsigned)t.tap * (unsigned)Cout); }
+  __device__ __forceinline__ u16 at(const Row& r, TapCh t) const { return gz[off(t) + r.co]; }
   static constexpr int kMode = 2;
   __host__ __device__ __forceinline__ bool vec() const { return Cout % 8 == 0; }
   __device__ __forceinline__ uint4 load_rows8(long m0, TapCh t) const {
-    return *(const uint4*)(gz + (long)t.tap * Cout + m0);
+    return *(const uint4*)(gz + off(t) + m0);
   }
 };
 
@@ -219,52 +231,93 @@ struct ClassRows {
 
 constexpr int kBM = 64, kBN = 64, kBK = 32, kLdsPad = 8;
 
-// C_z[rowmap(m)][n] = sum_{k in chunk z} A(m, k) B(k, n); C_z = C + z * Mout * N.
-// Operand tiles are staged in LDS as [row][k].  Load modes per operand: 0 one
-// element at a time; 1 eight consecutive k of a row in one 16-byte load; 2 eight
-// consecutive rows at one k in one 16-byte load (the operand is contiguous along
-// its rows).
+__device__ __forceinline__ float gelu_f(float z) { return 0.5f * z * (1.f + erff(z * 0.70710678118654752f)); }
+__device__ __forceinline__ float gelu_grad_f(float z) {
+  return 0.5f * (1.f + erff(z * 0.70710678118654752f)) + z * expf(-0.5f * z * z) * 0.39894228040143268f;
+}
+
+// Where a tile's FP32 results go.  StoreC: C_z[orow][n] (z the split-K chunk,
+// Mout rows per chunk).  StoreBiasGelu (forward convolutions): the
+// pre-activation z = v + b[n] in FP32 and a = BF16(GELU(z)), the same
+// arithmetic as a separate bias-GELU pass over C.
+struct StoreC {
+  float* C;
+  long Mout, N;
+  __device__ __forceinline__ void operator()(int zi, long orow, long col, float v) const {
+    C[((long)zi * Mout + orow) * N + col] = v;
+  }
+};
+struct StoreBiasGelu {
+  float* z;
+  u16* a;
+  const float* b;
+  long N;
+  __device__ __forceinline__ void operator()(int, long orow, long col, float v) const {
+    const float t = v + b[col];
+    const long i = orow * N + col;
+    z[i] = t;
+    a[i] = f2bf(gelu_f(t));
+  }
+};
+
+// (tap, channel) of K index k with `ch` channels per tap; K indices stay
+// below 2^31 (checked on the host), so 32-bit arithmetic.
+__device__ __forceinline__ TapCh tapch(long k, int ch) {
+  const unsigned u = (unsigned)k, c = (unsigned)ch;
+  const unsigned q = u / c;
+  return TapCh{(int)q, (int)(u - q * c)};
+}
+// the same advanced by kBK (q = kBK / ch, r = kBK % ch)
+__device__ __forceinline__ void tapch_step(TapCh& t, int ch, int q, int r) {
+  t.tap += q;
+  t.ch += r;
+  if (t.ch >= ch) { t.ch -= ch; ++t.tap; }
+}
+
+// C[rowmap(m)][n] = sum_{k in [kbeg, kend)} A(m, k) B(k, n) for the 64 x 64
+// tile at (m0, n0).  Operand tiles are staged in LDS as [row][k].  Load modes
+// per operand: 0 one element at a time; 1 eight consecutive k of a row in one
+// 16-byte load; 2 eight consecutive rows at one k in one 16-byte load (the
+// operand is contiguous along its rows).  Each thread's next K-tile is loaded
+// into registers before the current tile's MFMAs, so the global loads are in
+// flight while the matrix cores run.
 template <class G, int MODE>
-__device__ __forceinline__ void stage_tile(const G& g, const typename G::Row& r, bool row_ok,
-                                           bool rows8_ok, long row8, long k0, long kend, int lk,
-                                           int kk, int lr, int lr8, int ch,
-                                           u16 (*T)[kBK + kLdsPad]) {
+__device__ __forceinline__ uint4 fetch_tile(const G& g, const typename G::Row& r, bool row_ok,
+                                            bool rows8_ok, long row8, long k, long kend, TapCh tc,
+                                            int ch) {
+  uint4 v = make_uint4(0, 0, 0, 0);
   if constexpr (MODE == 2) {
-    const long k = k0 + kk;
-    uint4 v = make_uint4(0, 0, 0, 0);
-    if (rows8_ok && k < kend) v = g.load_rows8(row8, TapCh{(int)(k / ch), (int)(k % ch)});
+    if (rows8_ok && k < kend) v = g.load_rows8(row8, tc);
+  } else if constexpr (MODE == 1) {
+    if (row_ok && k < kend) v = g.load8(r, tc);
+  } else {
+    u16* pv = (u16*)&v;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      pv[i] = (row_ok && k + i < kend) ? g.at(r, tc) : (u16)0;
+      if (++tc.ch == ch) { tc.ch = 0; ++tc.tap; }
+    }
+  }
+  return v;
+}
+template <int MODE>
+__device__ __forceinline__ void put_tile(u16 (*T)[kBK + kLdsPad], uint4 v, int lr, int lk, int lr8, int kk) {
+  if constexpr (MODE == 2) {
     const u16* pv = (const u16*)&v;
 #pragma unroll
     for (int i = 0; i < 8; ++i) T[lr8 + i][kk] = pv[i];
-  } else if constexpr (MODE == 1) {
-    const long kf = k0 + lk;
-    uint4 v = make_uint4(0, 0, 0, 0);
-    if (row_ok && kf < kend) v = g.load8(r, TapCh{(int)(kf / ch), (int)(kf % ch)});
-    *(uint4*)&T[lr][lk] = v;
   } else {
-    const long kf = k0 + lk;
-    TapCh tc{(int)(kf / ch), (int)(kf % ch)};
-    u16 v[8];
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      v[i] = (row_ok && kf + i < kend) ? g.at(r, tc) : (u16)0;
-      if (++tc.ch == ch) { tc.ch = 0; ++tc.tap; }
-    }
-#pragma unroll
-    for (int i = 0; i < 8; ++i) T[lr][lk + i] = v[i];
+    *(uint4*)&T[lr][lk] = v;
   }
 }
 
-template <class GA, class GB, class RM, int AM, int BM>
-__global__ __launch_bounds__(256) void k_gemm_bf16(GA ga, GB gb, RM rowmap, float* __restrict__ C,
-                                                   long M, long N, long K, long kchunk, long Mout) {
+template <class GA, class GB, class RM, class EP, int AM, int BM>
+__device__ __forceinline__ void gemm_tile(const GA& ga, const GB& gb, const RM& rowmap, const EP& ep, int zi,
+                                          long M, long N, long kbeg, long kend, long m0, long n0) {
   __shared__ __attribute__((aligned(16))) u16 As[kBM][kBK + kLdsPad];
   __shared__ __attribute__((aligned(16))) u16 Bs[kBN][kBK + kLdsPad];
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int wm = wave >> 1, wn = wave & 1;
-  const long m0 = (long)blockIdx.x * kBM, n0 = (long)blockIdx.y * kBN;
-  const long kbeg = (long)blockIdx.z * kchunk;
-  const long kend = min(K, kbeg + kchunk);
   f32x4 acc[2][2];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
@@ -278,10 +331,22 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GA ga, GB gb, RM rowmap, floa
   const typename GA::Row ra = ga.row(am ? m0 + lr : 0);
   const typename GB::Row rb = gb.row(bn ? n0 + lr : 0);
   const int ca = ga.chans(), cb = gb.chans();
+  const int qa = kBK / ca, rma = kBK % ca, qb = kBK / cb, rmb = kBK % cb;
+  // this thread's K offset within a tile, per operand
+  const int oa = AM == 2 ? kk : lk, ob = BM == 2 ? kk : lk;
+  TapCh ta = tapch(kbeg + oa, ca), tb = tapch(kbeg + ob, cb);
+  uint4 va = fetch_tile<GA, AM>(ga, ra, am, am8, m0 + lr8, kbeg + oa, kend, ta, ca);
+  uint4 vb = fetch_tile<GB, BM>(gb, rb, bn, bn8, n0 + lr8, kbeg + ob, kend, tb, cb);
   for (long k0 = kbeg; k0 < kend; k0 += kBK) {
-    stage_tile<GA, AM>(ga, ra, am, am8, m0 + lr8, k0, kend, lk, kk, lr, lr8, ca, As);
-    stage_tile<GB, BM>(gb, rb, bn, bn8, n0 + lr8, k0, kend, lk, kk, lr, lr8, cb, Bs);
+    put_tile<AM>(As, va, lr, lk, lr8, kk);
+    put_tile<BM>(Bs, vb, lr, lk, lr8, kk);
     __syncthreads();
+    if (k0 + kBK < kend) {
+      tapch_step(ta, ca, qa, rma);
+      tapch_step(tb, cb, qb, rmb);
+      va = fetch_tile<GA, AM>(ga, ra, am, am8, m0 + lr8, k0 + kBK + oa, kend, ta, ca);
+      vb = fetch_tile<GB, BM>(gb, rb, bn, bn8, n0 + lr8, k0 + kBK + ob, kend, tb, cb);
+    }
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
       const bf16x8 a = *(const bf16x8*)&As[wm * 32 + i * 16 + (lane & 15)][(lane >> 4) * 8];
@@ -293,7 +358,6 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GA ga, GB gb, RM rowmap, floa
     }
     __syncthreads();
   }
-  float* Cz = C + (long)blockIdx.z * Mout * N;
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -304,9 +368,18 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GA ga, GB gb, RM rowmap, floa
 #pragma unroll
       for (int j = 0; j < 2; ++j) {
         const long col = n0 + wn * 32 + j * 16 + (lane & 15);
-        if (col < N) Cz[orow * N + col] = acc[i][j][r];
+        if (col < N) ep(zi, orow, col, acc[i][j][r]);
       }
     }
+}
+
+// One GEMM, split-K chunk z = blockIdx.z of kchunk K indices.
+template <class GA, class GB, class RM, class EP, int AM, int BM>
+__global__ __launch_bounds__(256) void k_gemm_bf16(GA ga, GB gb, RM rowmap, EP ep, long M, long N, long K,
+                                                   long kchunk) {
+  const long kbeg = (long)blockIdx.z * kchunk;
+  gemm_tile<GA, GB, RM, EP, AM, BM>(ga, gb, rowmap, ep, (int)blockIdx.z, M, N, kbeg, min(K, kbeg + kchunk),
+                                    (long)blockIdx.x * kBM, (long)blockIdx.y * kBN);
 }
 
 // Every gather states its vector mode (kMode) and when it applies (vec()).
@@ -315,19 +388,19 @@ static int load_mode(const G& g) {
   return g.vec() ? G::kMode : 0;
 }
 
-template <class GA, class GB, class RM = IdentityRows>
-static hipError_t gemm(GA ga, GB gb, float* C, long M, long N, long K, int splits, hipStream_t s,
-                       const char* tag, RM rowmap = RM(), long Mout = -1) {
+template <class GA, class GB, class RM = IdentityRows, class EP>
+static hipError_t gemm_ep(GA ga, GB gb, EP ep, long M, long N, long K, int splits, hipStream_t s,
+                          const char* tag, RM rowmap = RM()) {
+  if (K >= (1L << 31)) return hipErrorInvalidValue;   // 32-bit K indices
   long kchunk = (K + splits - 1) / splits;
   kchunk = (kchunk + kBK - 1) / kBK * kBK;
   const int z = (int)((K + kchunk - 1) / kchunk);
   dim3 grid((unsigned)((M + kBM - 1) / kBM), (unsigned)((N + kBN - 1) / kBN), (unsigned)z);
   const int am = load_mode(ga), bm = load_mode(gb);
-  const long mo = Mout < 0 ? M : Mout;
   ScopedTiming _t(tag, s);
-#define WO_GEMM(A_, B_)                                                                            \
-  hipLaunchKernelGGL((k_gemm_bf16<GA, GB, RM, A_, B_>), grid, dim3(256), 0, s, ga, gb, rowmap, C, M, \
-                     N, K, kchunk, mo)
+#define WO_GEMM(A_, B_)                                                                              \
+  hipLaunchKernelGGL((k_gemm_bf16<GA, GB, RM, EP, A_, B_>), grid, dim3(256), 0, s, ga, gb, rowmap, ep, M, \
+                     N, K, kchunk)
   if (am && bm) WO_GEMM(GA::kMode, GB::kMode);
   else if (am) WO_GEMM(GA::kMode, 0);
   else if (bm) WO_GEMM(0, GB::kMode);
@@ -336,9 +409,36 @@ static hipError_t gemm(GA ga, GB gb, float* C, long M, long N, long K, int split
   return hipGetLastError();
 }
 
-// Input gradient as 8 GEMMs, one per parity class of input positions.
+template <class GA, class GB>
+static hipError_t gemm(GA ga, GB gb, float* C, long M, long N, long K, int splits, hipStream_t s,
+                       const char* tag) {
+  return gemm_ep(ga, gb, StoreC{C, M, N}, M, N, K, splits, s, tag);
+}
+
+// Input gradient: the 8 GEMMs of the parity classes of input positions in one
+// launch, class = blockIdx.z (workgroups past a class's rows exit).
+struct DgradClasses {
+  GatherCol2imClass a[8];
+  GatherWTClass b[8];
+  long M[8], K[8];
+};
+
+template <int AM, int BM>
+__global__ __launch_bounds__(256) void k_gemm_dgrad(DgradClasses cl, float* __restrict__ out, long N,
+                                                    long Mout) {
+  const int c = (int)blockIdx.z;
+  const long m0 = (long)blockIdx.x * kBM;
+  if (m0 >= cl.M[c]) return;
+  gemm_tile<GatherCol2imClass, GatherWTClass, ClassRows, StoreC, AM, BM>(
+      cl.a[c], cl.b[c], ClassRows{cl.a[c]}, StoreC{out, Mout, N}, 0, cl.M[c], N, 0, cl.K[c], m0,
+      (long)blockIdx.y * kBN);
+}
+
 static hipError_t dgrad_classes(const u16* gz, const u16* w, ConvGeom gout, int Cin, int N,
                                 float* out, hipStream_t s) {
+  DgradClasses cl;
+  int nc = 0;
+  long mmax = 0;
   for (int cls = 0; cls < 8; ++cls) {
     GatherCol2imClass a;
     a.gz = gz;
@@ -347,14 +447,26 @@ static hipError_t dgrad_classes(const u16* gz, const u16* w, ConvGeom gout, int 
     a.cd = (gout.D - a.pd + 1) / 2; a.ch = (gout.H - a.ph + 1) / 2; a.cw = (gout.W - a.pw + 1) / 2;
     if (a.cd <= 0 || a.ch <= 0 || a.cw <= 0) continue;
     a.nd = a.pd ? 2 : 1; a.nh = a.ph ? 2 : 1; a.nw = a.pw ? 2 : 1;
-    const long M = (long)N * a.cd * a.ch * a.cw;
-    const long K = (long)a.nd * a.nh * a.nw * gout.C;
-    GatherWTClass b{w, Cin, gout.C, a.nd, a.nh, a.nw};
-    hipError_t e = gemm(a, b, out, M, Cin, K, 1, s, "k_gemm_conv_dgrad", ClassRows{a},
-                        (long)N * gout.D * gout.H * gout.W);
-    if (e != hipSuccess) return e;
+    cl.a[nc] = a;
+    cl.b[nc] = GatherWTClass{w, Cin, gout.C, a.nd, a.nh, a.nw};
+    cl.M[nc] = (long)N * a.cd * a.ch * a.cw;
+    cl.K[nc] = (long)a.nd * a.nh * a.nw * gout.C;
+    mmax = std::max(mmax, cl.M[nc]);
+    ++nc;
   }
-  return hipSuccess;
+  if (nc == 0) return hipSuccess;
+  const long Mout = (long)N * gout.D * gout.H * gout.W;
+  if (Mout >= (1L << 31)) return hipErrorInvalidValue;   // 32-bit position arithmetic
+  dim3 grid((unsigned)((mmax + kBM - 1) / kBM), (unsigned)((Cin + kBN - 1) / kBN), (unsigned)nc);
+  const int am = load_mode(cl.a[0]), bm = load_mode(cl.b[0]);
+  ScopedTiming _t("k_gemm_conv_dgrad", s);
+#define WO_DG(A_, B_) hipLaunchKernelGGL((k_gemm_dgrad<A_, B_>), grid, dim3(256), 0, s, cl, out, (long)Cin, Mout)
+  if (am && bm) WO_DG(GatherCol2imClass::kMode, GatherWTClass::kMode);
+  else if (am) WO_DG(GatherCol2imClass::kMode, 0);
+  else if (bm) WO_DG(0, GatherWTClass::kMode);
+  else WO_DG(0, 0);
+#undef WO_DG
+  return hipGetLastError();
 }
 
 static int splits_used(long K, int splits) {
@@ -408,21 +520,6 @@ static hipError_t reduce_parts(const float* part, int z, long n, float* out, hip
 }
 
 // ------------------------------------------------------------------ elementwise
-
-__device__ __forceinline__ float gelu_f(float z) { return 0.5f * z * (1.f + erff(z * 0.70710678118654752f)); }
-__device__ __forceinline__ float gelu_grad_f(float z) {
-  return 0.5f * (1.f + erff(z * 0.70710678118654752f)) + z * expf(-0.5f * z * z) * 0.39894228040143268f;
-}
-
-// z = C + b[c] (FP32), a = BF16(GELU(z)); C and z may alias.
-__global__ void k_bias_gelu(const float* C, const float* __restrict__ b, long P, int Co, float* z,
-                            u16* __restrict__ a) {
-  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= P * Co) return;
-  const float v = C[i] + b[i % Co];
-  z[i] = v;
-  a[i] = f2bf(gelu_f(v));
-}
 
 // gz = BF16(ga * GELU'(z)) over P positions x Co channels (Co divides 256), and
 // the bias gradient's first stage: workgroup g sums the rounded gz of its rows
@@ -643,10 +740,11 @@ static Net make_net(int N, int Z, int Y, int X) {
 
 long cnn_param_count() { return make_net(1, 32, 64, 64).nparam; }
 
-// Workspace for a batch: BF16 input and activations, FP32 pre-activations and
-// GEMM outputs, BF16 gradients, split-K partials, head buffers, BF16 weights.
+// Workspace for a batch: BF16 input and activations, FP32 pre-activations,
+// FP32 input gradients, BF16 gradients, split-K partials, head buffers, BF16
+// weights.
 struct CnnWs {
-  size_t x, a[kCnnLayers], z[kCnnLayers], c, gz, ga, part, pbf, grad, head, nrm, total;
+  size_t x, a[kCnnLayers], z[kCnnLayers], gz, ga, part, pbf, grad, head, nrm, total;
 };
 
 static size_t al(size_t x) { return (x + 255) / 256 * 256; }
@@ -675,7 +773,6 @@ static CnnWs cnn_ws(const Net& net) {
     maxpart = std::max(maxpart, (long)splits_used(L.P_out, wgrad_splits(L.P_out, L.Cout, 27L * L.Cin)) * L.Cout * 27 * L.Cin);
     maxpart = std::max(maxpart, (long)kBiasPartsMax * L.Cout);
   }
-  w.c = take(maxc * sizeof(float));
   w.gz = take(maxg * sizeof(u16));
   w.ga = take(maxc * sizeof(float));
   w.part = take(maxpart * sizeof(float));
@@ -698,7 +795,6 @@ int cnn_run(const float* params, const float* x, int N, int Z, int Y, int X, con
   const CnnWs W = cnn_ws(net);
   char* w = (char*)ws;
   u16* xb = (u16*)(w + W.x);
-  float* C = (float*)(w + W.c);
   u16* gz = (u16*)(w + W.gz);
   float* ga = (float*)(w + W.ga);
   float* part = (float*)(w + W.part);
@@ -724,14 +820,12 @@ int cnn_run(const float* params, const float* x, int N, int Z, int Y, int X, con
   for (int l = 0; l < kCnnLayers; ++l) {
     const Layer& L = net.L[l];
     const long K = 27L * L.Cin;
-    WO_HIP_CHECK(gemm(GatherIm2col{a_in, L.g}, GatherRows{pbf + L.w_off, K, L.Cin}, C, L.P_out, L.Cout,
-                      K, 1, s, "k_gemm_conv_fwd"));
     float* z = (float*)(w + W.z[l]);
     u16* a = (u16*)(w + W.a[l]);
-    { ScopedTiming _tm("k_bias_gelu", s);
-    hipLaunchKernelGGL(k_bias_gelu, dim3(blocks(L.P_out * L.Cout, 256)), dim3(256), 0, s, C,
-                       params + L.b_off, L.P_out, L.Cout, z, a);
-    }
+    // the GEMM's epilogue adds the bias and applies GELU (z and a written directly)
+    WO_HIP_CHECK(gemm_ep(GatherIm2col{a_in, L.g}, GatherRows{pbf + L.w_off, K, L.Cin},
+                         StoreBiasGelu{z, a, params + L.b_off, L.Cout}, L.P_out, L.Cout, K, 1, s,
+                         "k_gemm_conv_fwd"));
     a_in = a;
   }
   { ScopedTiming _tm("k_head", s);
@@ -936,9 +1030,10 @@ int wo_crop_stacks(const float* in, int32_t n, int32_t nz, int32_t ny, int32_t n
   return WO_OK;
 }
 
+// the kernels index positions (batch included) in 32 bits
 static bool cnn_shape_ok(int32_t batch, int32_t nz, int32_t ny, int32_t nx) {
   return batch >= 1 && batch <= 65535 && nz >= 1 && ny >= 1 && nx >= 1 && nz <= 1024 && ny <= 4096 &&
-         nx <= 4096;
+         nx <= 4096 && (long)batch * nz * ny * nx < (1L << 31);
 }
 
 size_t wo_cnn_workspace_size(int32_t batch, int32_t nz, int32_t ny, int32_t nx) {
@@ -981,7 +1076,7 @@ int wo_cnn_train_step(float* params, float* adam_m, float* adam_v, int32_t t, do
 
 static bool conv_ok(int N, int D, int H, int W, int Cin, int Cout) {
   return N >= 1 && D >= 1 && H >= 1 && W >= 1 && Cin >= 1 && Cout >= 1 && Cin <= 4096 &&
-         Cout <= 4096;
+         Cout <= 4096 && (long)N * D * H * W < (1L << 31);
 }
 
 int wo_conv3d_forward(const uint16_t* x, const uint16_t* w, int32_t N, int32_t D, int32_t H,

@@ -25,6 +25,8 @@ __global__ __launch_bounds__(1024) void k_rows_r2c(const float* __restrict__ in,
   extern __shared__ float2 smem[];
   float2* tw = smem;
   float2* buf = smem + X;
+  // element offsets of the line's rows (row index times the row pitch), -1
+  // for a missing row: no 64-bit multiply per element
   __shared__ long rin[2 * 64], rout[2 * 64];
   const int tid = threadIdx.x, nthr = blockDim.x;
   const long nrows = g.rows_per_group * g.ngroups;
@@ -32,8 +34,8 @@ __global__ __launch_bounds__(1024) void k_rows_r2c(const float* __restrict__ in,
   const int nl = (int)min((long)lines_per_wg, nlines - line0);
   for (int t = tid; t < 2 * nl; t += nthr) {
     const long r = 2 * line0 + t;
-    rin[t] = r < nrows ? group_row(r, g.rows_per_group, g.in_stride) : -1;
-    rout[t] = r < nrows ? group_row(r, g.rows_per_group, g.out_stride) : -1;
+    rin[t] = r < nrows ? group_row(r, g.rows_per_group, g.in_stride) * X : -1;
+    rout[t] = r < nrows ? group_row(r, g.rows_per_group, g.out_stride) * OP : -1;
   }
   __syncthreads();
   const int Xc = NS > 0 ? NS : X;   // compile-time length for the index arithmetic
@@ -43,7 +45,7 @@ __global__ __launch_bounds__(1024) void k_rows_r2c(const float* __restrict__ in,
   // zeroed after the loads
   auto load = [&](int l, int i) {
     const long ra = rin[2 * l], rb = rin[2 * l + 1];
-    return make_float2(in[ra * X + i], in[(rb >= 0 ? rb : ra) * X + i]);
+    return make_float2(in[ra + i], in[(rb >= 0 ? rb : ra) + i]);
   };
   auto finish = [&](int l, int, float2 v) { return make_float2(v.x, rin[2 * l + 1] >= 0 ? v.y : 0.f); };
   if constexpr (NS > 0) {
@@ -75,8 +77,8 @@ __global__ __launch_bounds__(1024) void k_rows_r2c(const float* __restrict__ in,
       const float2 zm = buf[l * LS + row_slot(k == 0 ? 0 : Xc - k, PS)];
       const float2 A = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y));
       const float2 B = make_float2(0.5f * (zk.y + zm.y), -0.5f * (zk.x - zm.x));
-      out[rout[2 * l] * OP + k] = A;
-      if (rout[2 * l + 1] >= 0) out[rout[2 * l + 1] * OP + k] = B;
+      out[rout[2 * l] + k] = A;
+      if (rout[2 * l + 1] >= 0) out[rout[2 * l + 1] + k] = B;
     }
   }
 }
@@ -94,10 +96,10 @@ __global__ __launch_bounds__(1024) void k_rows_c2r(const float2* __restrict__ in
   const long nrows = g.rows_per_group * g.ngroups;
   const long line0 = (long)blockIdx.x * lines_per_wg;
   const int nl = (int)min((long)lines_per_wg, nlines - line0);
-  for (int t = tid; t < 2 * nl; t += nthr) {
+  for (int t = tid; t < 2 * nl; t += nthr) {   // element offsets, as in k_rows_r2c
     const long r = 2 * line0 + t;
-    rin[t] = r < nrows ? group_row(r, g.rows_per_group, g.in_stride) : -1;
-    rout[t] = r < nrows ? group_row(r, g.rows_per_group, g.out_stride) : -1;
+    rin[t] = r < nrows ? group_row(r, g.rows_per_group, g.in_stride) * IP : -1;
+    rout[t] = r < nrows ? group_row(r, g.rows_per_group, g.out_stride) * X : -1;
   }
   __syncthreads();
   const int Xc = NS > 0 ? NS : X;   // compile-time length for the index arithmetic
@@ -115,8 +117,8 @@ __global__ __launch_bounds__(1024) void k_rows_c2r(const float2* __restrict__ in
     const long ra = rin[2 * l], rb = rin[2 * l + 1];
     float2 A = make_float2(0.f, 0.f), B = A;
     if (kk < KT) {
-      A = in[ra * IP + kk];
-      B = in[(rb >= 0 ? rb : ra) * IP + kk];
+      A = in[ra + kk];
+      B = in[(rb >= 0 ? rb : ra) + kk];
     }
     return make_float4(A.x, A.y, B.x, B.y);
   };
@@ -130,8 +132,8 @@ __global__ __launch_bounds__(1024) void k_rows_c2r(const float2* __restrict__ in
     return make_float2(A.x - B.y, A.y + B.x);
   };
   auto store = [&](int l, int i, float2 v) {
-    out[rout[2 * l] * X + i] = v.x * scale;
-    if (rout[2 * l + 1] >= 0) out[rout[2 * l + 1] * X + i] = v.y * scale;
+    out[rout[2 * l] + i] = v.x * scale;
+    if (rout[2 * l + 1] >= 0) out[rout[2 * l + 1] + i] = v.y * scale;
   };
   if constexpr (NS > 0) {
     // first pass straight from memory, last pass straight to memory
@@ -676,7 +678,7 @@ __device__ __forceinline__ void freq_op(float2* cell, long cs, HF H, int Crt, in
       h[p] = H(0, p);
       den += h[p].x * h[p].x + h[p].y * h[p].y;
     }
-    const float sc = den > 0.f ? inv_n / den : 0.f;
+    const float sc = den > 0.f ? inv_n * __builtin_amdgcn_rcpf(den) : 0.f;   // hardware reciprocal
 #pragma unroll
     for (int p = 0; p < P; ++p) cell[p * cs] = cscale(cmulconj(xc, h[p]), sc);
     return;
@@ -707,7 +709,7 @@ __device__ __forceinline__ void freq_op(float2* cell, long cs, HF H, int Crt, in
   float2 F[P];
   if (P == 1) {
     const float den = m[0][0].x + eta;
-    F[0] = den > 0.f ? cscale(r[0], 1.f / den) : make_float2(0.f, 0.f);
+    F[0] = den > 0.f ? cscale(r[0], __builtin_amdgcn_rcpf(den)) : make_float2(0.f, 0.f);
   } else {
     chol_solve<P>(m, r, eta, F);
   }
@@ -801,7 +803,14 @@ __global__ __launch_bounds__(1024, NS > 0 ? 7 : 1) void k_zop(float2* __restrict
   const long mt0 = (gm.bank_band ? brow : row) * gm.Lt + col0;   // and in a bank plane
   const bool dc_tile = row == 0 && col0 == 0;
   const int weff = (int)min((long)W, gm.kt - col0);
-  const long ts = (long)Z * Mt;              // stride between (c, p) entries of the bank
+  // Element (plane, w) of the tile: a plane pitch is below 2^32 (checked on
+  // the host), so its offset is one 32 x 32 -> 64-bit multiply, not a 64-bit
+  // product per element.
+  float2* const st = sp + m0;
+  const float2* const tt = tp + mt0;
+  const unsigned ums = (unsigned)Ms, umt = (unsigned)Mt;
+  auto soff = [&](int plane) { return (long)((unsigned long)(unsigned)plane * ums); };
+  auto toff = [&](int plane) { return (long)((unsigned long)(unsigned)plane * umt); };
   // Issue this thread's transfer-function loads first: they complete while the
   // data tile is loaded and transformed.  Frequency f = tid + i * nthr.
   const int nfreq = Zc * W;
@@ -818,7 +827,7 @@ __global__ __launch_bounds__(1024, NS > 0 ? 7 : 1) void k_zop(float2* __restrict
       const int f = tid + i * nthr;
       if (i < fpt && f < nfreq) {
         const int z = f >> wsh, w = f & (W - 1);
-        hreg[j] = w < weff ? tp[cp * ts + (long)z * Mt + mt0 + w] : make_float2(0.f, 0.f);
+        hreg[j] = w < weff ? tt[toff(cp * Zc + z) + w] : make_float2(0.f, 0.f);
       }
     }
   }
@@ -829,7 +838,7 @@ __global__ __launch_bounds__(1024, NS > 0 ? 7 : 1) void k_zop(float2* __restrict
         buf, cin * W, CH * W, 1, pow2_shift(cin * W), -1.f, tid, nthr,
         [&](int l, int z) {
           const int ch = l >> wsh, w = l & (W - 1);
-          return w < weff ? sp[((long)ch * Z + z) * Ms + m0 + w] : make_float2(0.f, 0.f);
+          return w < weff ? st[soff(ch * Zc + z) + w] : make_float2(0.f, 0.f);
         },
         [&] { fill_twiddles(tw, Z, tid, nthr); });
     static_passes<NS, 0, true, kEmax, false, false, 1, StaticPlan<NS>::passes()>(
@@ -843,7 +852,7 @@ __global__ __launch_bounds__(1024, NS > 0 ? 7 : 1) void k_zop(float2* __restrict
       if (e < cin * Zc * W) {
         const int w = e & (W - 1), r = e >> wsh;
         const int z = r % Zc, ch = r / Zc;
-        t[i] = w < weff ? sp[((long)ch * Z + z) * Ms + m0 + w] : make_float2(0.f, 0.f);
+        t[i] = w < weff ? st[soff(ch * Zc + z) + w] : make_float2(0.f, 0.f);
       }
     }
     fill_twiddles(tw, Z, tid, nthr);
@@ -891,9 +900,9 @@ __global__ __launch_bounds__(1024, NS > 0 ? 7 : 1) void k_zop(float2* __restrict
     for (int f = tid; f < nfreq; f += nthr) {
       const int z = f >> wsh, w = f & (W - 1);
       if (w >= weff) continue;
-      const float2* hp = tp + (long)z * Mt + mt0 + w;
+      const float2* hp = tt + w;
       if constexpr (RED) {
-        const float2 hph = hp[0], hab = hp[ts];
+        const float2 hph = hp[toff(z)], hab = hp[toff(Zc + z)];
         const float* kf = &cpl[patch].k[0][0][0];
         if (mode == kModeSolve)
           pol5_solve(buf + (long)z * CH * W + w, W, hph, hab, cpl + patch, eta, bp,
@@ -906,7 +915,7 @@ __global__ __launch_bounds__(1024, NS > 0 ? 7 : 1) void k_zop(float2* __restrict
                          C, mode, eta, bp, z == 0 && dc_tile && w == 0, n_full, inv_n);
       } else {
         freq_op<P, CT>(buf + (long)z * CH * W + w, W,
-                       [&](int c, int p) { return hp[(long)(c * P + p) * ts]; }, C, mode, eta, bp,
+                       [&](int c, int p) { return hp[toff((c * P + p) * Zc + z)]; }, C, mode, eta, bp,
                        z == 0 && dc_tile && w == 0, n_full, inv_n);
       }
     }
@@ -920,7 +929,7 @@ __global__ __launch_bounds__(1024, NS > 0 ? 7 : 1) void k_zop(float2* __restrict
         buf, cout * W, CH * W, 1, pow2_shift(cout * W), tw, 1.f, tid, nthr,
         [&](int l, int z, float2 v) {
           const int ch = l >> wsh, w = l & (W - 1);
-          if (w < weff) sp[((long)ch * Z + z) * Ms + m0 + w] = v;
+          if (w < weff) st[soff(ch * Zc + z) + w] = v;
         });
   } else {
     fft_lines<NS, 0, true>(buf, LdsLines{cout * W, CH * W, 1, true, pow2_shift(cout * W)}, plan, tw, 1.f,
@@ -941,7 +950,7 @@ __global__ __launch_bounds__(1024, NS > 0 ? 7 : 1) void k_zop(float2* __restrict
       if (e < cout * Zc * W) {
         const int w = e & (W - 1), r = e >> wsh;
         const int z = r % Zc, ch = r / Zc;
-        if (w < weff) sp[((long)ch * Z + z) * Ms + m0 + w] = t[i];
+        if (w < weff) st[soff(ch * Zc + z) + w] = t[i];
       }
     }
   }
@@ -1021,6 +1030,7 @@ hipError_t launch_zop(float2* spec, const float2* tf, int C, int P, int Z, long 
   gm.Mt = gm.bank_band ? (long)nbr * bc.kt : M;
   gm.nb = nbr;
   gm.ky = nbr == bc.Y ? bc.Y : bc.ky;
+  if (gm.Ms >= (1L << 32) || gm.Mt >= (1L << 32)) return hipErrorInvalidValue;   // 32-bit plane offsets
   gm.tiles_row = (int)((bc.kt + W - 1) / W);
   const long tiles = (long)nbr * gm.tiles_row;
   const long nwg = tiles * npatch;
