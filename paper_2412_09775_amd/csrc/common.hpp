@@ -173,12 +173,37 @@ __device__ __forceinline__ void dft_small(float2* v, float s) {
   else if constexpr (R == 8) dft8(v, s);
 }
 
-// Twiddles tw[m] = exp(-2 pi i m / n), m < n, computed in FP64.
+// Twiddles tw[m] = exp(-2 pi i m / n), m < n, from FP64 sines and cosines.
+// When 8 divides n only the angles a = 2 pi r / n in [0, pi/4] (r <= n/8) are
+// evaluated: with (c, s) = (cos a, sin a), the angles q pi/2 + a and
+// q pi/2 - a (q = 0..3, 1..4) have cos and sin equal to c and s up to swaps
+// and signs, so each evaluation fills up to eight entries exactly, and a
+// workgroup computes n/8 + 1 sine-cosine pairs instead of n.
 __device__ __forceinline__ void fill_twiddles(float2* tw, int n, int tid, int nthr) {
-  for (int m = tid; m < n; m += nthr) {
-    double sn, cs;
-    sincospi(-2.0 * (double)m / (double)n, &sn, &cs);
-    tw[m] = make_float2((float)cs, (float)sn);
+  if ((n & 7) != 0) {
+    for (int m = tid; m < n; m += nthr) {
+      double sn, cs;
+      sincospi(-2.0 * (double)m / (double)n, &sn, &cs);
+      tw[m] = make_float2((float)cs, (float)sn);
+    }
+    return;
+  }
+  const int e = n >> 3, qn = n >> 2;
+  for (int r = tid; r <= e; r += nthr) {
+    double sd, cd;
+    sincospi(2.0 * (double)r / (double)n, &sd, &cd);
+    const float c = (float)cd, s = (float)sd;
+    // exp(-i t) = (cos t, -sin t) for t = q pi/2 + a
+    tw[r] = make_float2(c, -s);
+    tw[qn + r] = make_float2(-s, -c);
+    tw[2 * qn + r] = make_float2(-c, s);
+    tw[3 * qn + r] = make_float2(s, c);
+    if (r > 0 && r < e) {   // t = q pi/2 - a (r = 0 and r = n/8 coincide with the above)
+      tw[qn - r] = make_float2(s, -c);
+      tw[2 * qn - r] = make_float2(-c, -s);
+      tw[3 * qn - r] = make_float2(-s, c);
+      tw[n - r] = make_float2(c, s);
+    }
   }
 }
 

@@ -48,10 +48,13 @@ __global__ __launch_bounds__(1024) void k_rows_r2c(const float* __restrict__ in,
     return make_float2(in[ra + i], in[(rb >= 0 ? rb : ra) + i]);
   };
   auto finish = [&](int l, int, float2 v) { return make_float2(v.x, rin[2 * l + 1] >= 0 ? v.y : 0.f); };
+  // twiddles before the loads: few threads evaluate them (symmetric fill), and
+  // nothing of it stays live while the loads are in flight
+  fill_twiddles(tw, Xc, tid, nthr);
   if constexpr (NS > 0) {
     // first pass straight from memory
     first_pass_in2<NS, 0, false, kEmax, true, false>(buf, nl, 1, LS, -1, -1.f, tid, nthr, load, finish,
-                                                     [&] { fill_twiddles(tw, X, tid, nthr); });
+                                                     [] {});
     static_passes<NS, 0, false, kEmax, true, false, 1, StaticPlan<NS>::passes()>(buf, nl, 1, LS, -1, tw,
                                                                                 -1.f, tid, nthr);
   } else {
@@ -61,7 +64,7 @@ __global__ __launch_bounds__(1024) void k_rows_r2c(const float* __restrict__ in,
     }, [&](int e, float2 v) { return finish(e / Xc, 0, v); }, [&](int e) {
       const int l = e / Xc;
       return l * LS + row_slot(e - l * Xc, PS);
-    }, [&] { fill_twiddles(tw, X, tid, nthr); });
+    }, [] {});
     __syncthreads();
     fft_lines<NS, 0, false, kEmax, true>(buf, LdsLines{nl, 1, LS, false, -1, true}, plan, tw, -1.f, tid,
                                          nthr);
@@ -135,11 +138,12 @@ __global__ __launch_bounds__(1024) void k_rows_c2r(const float2* __restrict__ in
     out[rout[2 * l] + i] = v.x * scale;
     if (rout[2 * l + 1] >= 0) out[rout[2 * l + 1] + i] = v.y * scale;
   };
+  fill_twiddles(tw, Xc, tid, nthr);   // before the loads, as in k_rows_r2c
   if constexpr (NS > 0) {
     // first pass straight from memory, last pass straight to memory
     constexpr int NP = StaticPlan<NS>::passes();
     first_pass_in2<NS, 0, false, kEmax, true, false>(buf, nl, 1, LS, -1, 1.f, tid, nthr, load, finish,
-                                                     [&] { fill_twiddles(tw, X, tid, nthr); });
+                                                     [] {});
     static_passes<NS, 0, false, kEmax, true, false, 1, NP - 1>(buf, nl, 1, LS, -1, tw, 1.f, tid, nthr);
     last_pass_out<NS, 0, false, kEmax, true, false>(buf, nl, 1, LS, -1, tw, 1.f, tid, nthr, store);
   } else {
@@ -149,7 +153,7 @@ __global__ __launch_bounds__(1024) void k_rows_c2r(const float2* __restrict__ in
     }, [&](int e, float4 v) {
       const int l = e / Xc;
       return finish(l, e - l * Xc, v);
-    }, slot, [&] { fill_twiddles(tw, X, tid, nthr); });
+    }, slot, [] {});
     __syncthreads();
     fft_lines<NS, 0, false, kEmax, true>(buf, LdsLines{nl, 1, LS, false, -1, true}, plan, tw, 1.f, tid,
                                          nthr);
@@ -301,13 +305,14 @@ __global__ __launch_bounds__(1024, 8) void k_cols(float2* __restrict__ data, int
   const int Nc = NS > 0 ? NS : N;
   auto ld_ok = [&](int l, int n) { return l < weff && (band != 2 || in_band(n, ky, nb, Nc)); };
   auto st_ok = [&](int l, int n) { return l < weff && (band != 1 || in_band(n, ky, nb, Nc)); };
+  fill_twiddles(tw, Nc, tid, nthr);   // before the loads, as in the row passes
   if constexpr (NS > 0) {
     // line l = column m0 + l; first pass straight from memory, last pass
     // straight to memory
     fft_direct<NS, WS, true, kEmax, false>(
         buf, W, W, 1, wsh, tw, sign, tid, nthr,
         [&](int l, int n) { return ld_ok(l, n) ? base[(long)n * M + m0 + l] : make_float2(0.f, 0.f); },
-        [&] { fill_twiddles(tw, Nc, tid, nthr); },
+        [] {},
         [&](int l, int n, float2 v) {
           if (st_ok(l, n)) base[(long)n * M + m0 + l] = v;
         });
@@ -315,7 +320,7 @@ __global__ __launch_bounds__(1024, 8) void k_cols(float2* __restrict__ data, int
     gather_to_lds(buf, Nc * W, tid, nthr, [&](int e) {
       const int n = e >> wsh, w = e & (W - 1);
       return ld_ok(w, n) ? base[(long)n * M + m0 + w] : make_float2(0.f, 0.f);
-    }, [&] { fill_twiddles(tw, Nc, tid, nthr); });
+    }, [] {});
     __syncthreads();
     fft_lines<NS, WS, true>(buf, LdsLines{W, W, 1, true, wsh}, plan, tw, sign, tid, nthr);
     scatter_from_lds(buf, Nc * W, tid, nthr, [&](int e, float2 v) {
@@ -359,10 +364,10 @@ __global__ __launch_bounds__(1024) void k_cols_loop(float2* __restrict__ data, l
                                                                : make_float2(0.f, 0.f);
     });
   };
+  fill_twiddles(tw, NS, tid, nthr);   // before the loads, as in the row passes
   FirstPassRaw<NS, kEmax, false> raw;
   long t = xcd_block();   // G <= total: every workgroup has a first tile
   issue(raw, t);
-  fill_twiddles(tw, NS, tid, nthr);
   while (t < total) {
     long m0;
     int weff;
@@ -507,8 +512,8 @@ __global__ __launch_bounds__(1024) void k_cols_expand(const float2* __restrict__
   const float2* sb = src + g * N * ms + (long)ys * kt + kx0;
   float2* db = dst + g * N * md + (band_out ? (long)b * kt : (long)y * Xh) + kx0;
   const int Nc = NS > 0 ? NS : N;
+  fill_twiddles(tw, Nc, tid, nthr);   // before the loads, as in the row passes
   auto mid = [&] {
-    fill_twiddles(tw, Nc, tid, nthr);
     const long r0 = bid * zrows, r1 = min(r0 + zrows, zrows_total);
     int yr = (int)(r0 % Y);
     for (long row = r0; row < r1; ++row) {
@@ -831,6 +836,7 @@ __global__ __launch_bounds__(1024, NS > 0 ? 7 : 1) void k_zop(float2* __restrict
       }
     }
   }
+  fill_twiddles(tw, Zc, tid, nthr);   // before the data loads, as in the row passes
   // LDS holds [z][ch][w]: line l = ch W + w, element z at z CH W
   if constexpr (NS > 0) {
     // first pass of the forward Z transform straight from memory
@@ -840,7 +846,7 @@ __global__ __launch_bounds__(1024, NS > 0 ? 7 : 1) void k_zop(float2* __restrict
           const int ch = l >> wsh, w = l & (W - 1);
           return w < weff ? st[soff(ch * Zc + z) + w] : make_float2(0.f, 0.f);
         },
-        [&] { fill_twiddles(tw, Z, tid, nthr); });
+        [] {});
     static_passes<NS, 0, true, kEmax, false, false, 1, StaticPlan<NS>::passes()>(
         buf, cin * W, CH * W, 1, pow2_shift(cin * W), tw, -1.f, tid, nthr);
   } else {
@@ -855,7 +861,6 @@ __global__ __launch_bounds__(1024, NS > 0 ? 7 : 1) void k_zop(float2* __restrict
         t[i] = w < weff ? st[soff(ch * Zc + z) + w] : make_float2(0.f, 0.f);
       }
     }
-    fill_twiddles(tw, Z, tid, nthr);
 #pragma unroll
     for (int i = 0; i < kEmax; ++i) {
       const int e = tid + i * nthr;
