@@ -760,6 +760,27 @@ __host__ __device__ __forceinline__ void source_centre(const DevOptics& o, doubl
 }
 
 // Axial PSF coordinate of plane k: FFT order for 3D models, centred planes for thin.
+// Plane chunks of the field kernel: runs of at most ZC consecutive planes that
+// never cross the jump of the wrapped axial order (3D models: plane
+// (nz + 1) / 2 follows the last non-negative z), so within a chunk the plane
+// position advances by dz from one plane to the next.
+__host__ __device__ __forceinline__ int z_split(const Sampling& sm) {
+  return sm.model == kLabelFreeThin ? 0 : (sm.nz + 1) / 2;
+}
+__host__ __device__ __forceinline__ int z_chunk_count(int Z, int zs, int ZC) {
+  return (zs + ZC - 1) / ZC + (Z - zs + ZC - 1) / ZC;
+}
+__host__ __device__ __forceinline__ void z_chunk_range(int Z, int zs, int ZC, int zc, int* zb, int* ze) {
+  const int n1 = (zs + ZC - 1) / ZC;
+  if (zc < n1) {
+    *zb = zc * ZC;
+    *ze = *zb + ZC < zs ? *zb + ZC : zs;
+  } else {
+    *zb = zs + (zc - n1) * ZC;
+    *ze = *zb + ZC < Z ? *zb + ZC : Z;
+  }
+}
+
 __device__ __forceinline__ double plane_z(int k, const Sampling& sm) {
   if (sm.model == kLabelFreeThin) return sm.dz * ((double)k - 0.5 * (double)(sm.nz - 1));
   const int ks = (k < (sm.nz + 1) / 2) ? k : k - sm.nz;

@@ -141,9 +141,12 @@ __global__ __launch_bounds__(1024) void k_tf_fields_y(const DevOptics* __restric
   const long bid = xcd_block();
   const long tile = bid % tiles_x;
   const long rest = bid / tiles_x;
-  const int nzc = (Z + ZC - 1) / ZC;
+  const int zsplit = z_split(sm);
+  const int nzc = z_chunk_count(Z, zsplit, ZC);
   const int zc = (int)(rest % nzc);
   const long patch = rest / nzc;
+  int zbeg, zend;
+  z_chunk_range(Z, zsplit, ZC, zc, &zbeg, &zend);
   const DevOptics o = opt[patch];
   constexpr bool fluor = NF == 1;   // one field (fluorescence) or A and B (label-free)
   constexpr int nf = NF;
@@ -215,30 +218,49 @@ __global__ __launch_bounds__(1024) void k_tf_fields_y(const DevOptics* __restric
         if (tid == 0) partials[patch * tiles_x + tile] = tot;
       }
     }
-    const int zend = min(Z, (zc + 1) * ZC);
-    for (int z = zc * ZC; z < zend; ++z) {
-      const double dzr = plane_z(z, sm) - o.defocus;
+    // The phase pi arg(z), arg = 2 kz (z - dz0) (+ 2 W), is linear in the plane
+    // position, which advances by dz within a chunk (chunks never cross the
+    // jump of the wrapped axial order): each element carries its field value
+    // of the current plane, the pupil factor times e^{i pi arg} (times i for
+    // B), evaluated directly at the chunk's first plane (FP64 argument
+    // reduction, FP32 sine and cosine) and then advanced plane by plane by
+    // the step e^{i pi 2 kz dz}, one complex multiply.  Over at most ZC - 1
+    // steps the products' rounding stays near 1e-6 relative.
+    float2 ph[B0][R0], st[B0][R0];
+    {
+      const double dzr = plane_z(zbeg, sm) - o.defocus;
+#pragma unroll
+      for (int b = 0; b < B0; ++b) {
+        const int j = tid + b * nthr;
+        const bool fa = ((j & (nl - 1)) >> wsh) == 0;   // A (or the fluorescence field), else B
+#pragma unroll
+        for (int r = 0; r < R0; ++r) {
+          ph[b][r] = st[b][r] = make_float2(0.f, 0.f);
+          if (j < nl * NB0 && fac[b][r] != 0.f) {
+            double arg = tkz[b][r] * dzr;
+            if constexpr (AB) arg += (double)ab2[b][r];
+            float sn, cs;
+            sincospif((float)(arg - 2.0 * rint(0.5 * arg)), &sn, &cs);
+            ph[b][r] = fa ? make_float2(fac[b][r] * cs, fac[b][r] * sn)
+                          : make_float2(-fac[b][r] * sn, fac[b][r] * cs);   // e^{i phi} (i g)
+            const double sa = tkz[b][r] * sm.dz;
+            sincospif((float)(sa - 2.0 * rint(0.5 * sa)), &sn, &cs);
+            st[b][r] = make_float2(cs, sn);
+          }
+        }
+      }
+    }
+    for (int z = zbeg; z < zend; ++z) {
 #pragma unroll
       for (int b = 0; b < B0; ++b) {
         const int j = tid + b * nthr;
         if (j < nl * NB0) {
           const int l = j & (nl - 1), k = j >> lsh;
-          const bool fa = (l >> wsh) == 0;   // A (or the fluorescence field), else B
           float2 v[R0];
 #pragma unroll
           for (int r = 0; r < R0; ++r) {
-            v[r] = make_float2(0.f, 0.f);
-            if (fac[b][r] != 0.f) {
-              // phase 2 pi kz (z - dz0): reduce the argument (in units of pi) in
-              // FP64 to [-1, 1], then evaluate sin/cos in FP32
-              double arg = tkz[b][r] * dzr;
-              if constexpr (AB) arg += (double)ab2[b][r];
-              const float rr = (float)(arg - 2.0 * rint(0.5 * arg));
-              float sn, cs;
-              sincospif(rr, &sn, &cs);
-              v[r] = fa ? make_float2(fac[b][r] * cs, fac[b][r] * sn)
-                        : make_float2(-fac[b][r] * sn, fac[b][r] * cs);   // e^{i phi} (i g)
-            }
+            v[r] = ph[b][r];
+            if (z + 1 < zend) ph[b][r] = cmul(ph[b][r], st[b][r]);
           }
           dft_small<R0>(v, 1.f);   // span 1: no twiddles
 #pragma unroll
@@ -323,8 +345,7 @@ __global__ __launch_bounds__(1024) void k_tf_fields_y(const DevOptics* __restric
         if (tid == 0) partials[patch * tiles_x + tile] = tot;
       }
     }
-    const int zend = min(Z, (zc + 1) * ZC);
-    for (int z = zc * ZC; z < zend; ++z) {
+    for (int z = zbeg; z < zend; ++z) {
       const double dzr = plane_z(z, sm) - o.defocus;
 #pragma unroll
       for (int i = 0; i < EPT; ++i) {
@@ -427,7 +448,7 @@ hipError_t launch_tf_fields_y(const DevOptics* opt, const Sampling& sm, int npat
   FftChoice fc;
   if (!fft_lookup(key, &fc) || !tf_fields_choice_ok(sm.nz, fc)) fc = tf_fields_default(sm.nz, tiles, npatch);
   const int ZC = fc.w;
-  const long nwg = tiles * ((sm.nz + ZC - 1) / ZC) * (long)npatch;
+  const long nwg = tiles * z_chunk_count(sm.nz, z_split(sm), ZC) * (long)npatch;
   const int thr = threads_for((long)LY * nf * W);
   const size_t lds = (size_t)(LY + LY * nf * W) * sizeof(float2);
   ScopedTiming _t("k_tf_fields_y", s);
