@@ -229,7 +229,7 @@ struct ClassRows {
 
 // ------------------------------------------------------------------ GEMM
 
-constexpr int kBM = 64, kBN = 64, kBK = 32, kLdsPad = 8;
+constexpr int kBM = 64, kBN = 64, kBK = 32, kLdsPad = 8;   // kBM x kBN: the default tile
 
 __device__ __forceinline__ float gelu_f(float z) { return 0.5f * z * (1.f + erff(z * 0.70710678118654752f)); }
 __device__ __forceinline__ float gelu_grad_f(float z) {
@@ -274,78 +274,106 @@ __device__ __forceinline__ void tapch_step(TapCh& t, int ch, int q, int r) {
   if (t.ch >= ch) { t.ch -= ch; ++t.tap; }
 }
 
-// C[rowmap(m)][n] = sum_{k in [kbeg, kend)} A(m, k) B(k, n) for the 64 x 64
-// tile at (m0, n0).  Operand tiles are staged in LDS as [row][k].  Load modes
-// per operand: 0 one element at a time; 1 eight consecutive k of a row in one
-// 16-byte load; 2 eight consecutive rows at one k in one 16-byte load (the
-// operand is contiguous along its rows).  Each thread's next K-tile is loaded
-// into registers before the current tile's MFMAs, so the global loads are in
-// flight while the matrix cores run.
-template <class G, int MODE>
-__device__ __forceinline__ uint4 fetch_tile(const G& g, const typename G::Row& r, bool row_ok,
-                                            bool rows8_ok, long row8, long k, long kend, TapCh tc,
-                                            int ch) {
-  uint4 v = make_uint4(0, 0, 0, 0);
-  if constexpr (MODE == 2) {
-    if (rows8_ok && k < kend) v = g.load_rows8(row8, tc);
-  } else if constexpr (MODE == 1) {
-    if (row_ok && k < kend) v = g.load8(r, tc);
-  } else {
-    u16* pv = (u16*)&v;
+// C[rowmap(m)][n] = sum_{k in [kbeg, kend)} A(m, k) B(k, n) for the TM x TN
+// tile at (m0, n0): 64 x 64, or 128 x 32 for narrow N (no MFMA on padding);
+// each of the 4 waves computes a 32 x 32 block as 2 x 2 MFMA tiles.  Operand
+// tiles are staged in LDS as [row][k], each operand in slots of 64 rows per
+// thread.  Load modes per operand: 0 one element at a time; 1 eight
+// consecutive k of a row in one 16-byte load; 2 eight consecutive rows at one
+// k in one 16-byte load (the operand is contiguous along its rows).  Each
+// thread's next K-tile is loaded into registers before the current tile's
+// MFMAs, so the global loads are in flight while the matrix cores run.
+template <class G, int MODE, int ROWS>
+struct Stage {
+  static constexpr int S = ROWS >= 64 ? ROWS / 64 : 1;   // 64-row slots per thread
+  typename G::Row r[S];
+  bool ok[S], ok8[S];
+  long row8[S];
+  uint4 v[S];
+  int lr, lk, kk, lr8, ch;
+  __device__ __forceinline__ bool mine(int i) const {   // this thread stages slot i
+    return (MODE == 2 ? lr8 : lr) + 64 * i < ROWS;
+  }
+  __device__ __forceinline__ void init(const G& g, long r0, long R, int t) {
+    lr = t >> 2; lk = (t & 3) * 8; kk = t & 31; lr8 = (t >> 5) * 8;
+    ch = g.chans();
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      pv[i] = (row_ok && k + i < kend) ? g.at(r, tc) : (u16)0;
-      if (++tc.ch == ch) { tc.ch = 0; ++tc.tap; }
+    for (int i = 0; i < S; ++i) {
+      const long rr = r0 + lr + 64 * i;
+      ok[i] = mine(i) && rr < R;
+      row8[i] = r0 + lr8 + 64 * i;
+      ok8[i] = mine(i) && row8[i] < R;
+      r[i] = g.row(ok[i] ? rr : 0);
     }
   }
-  return v;
-}
-template <int MODE>
-__device__ __forceinline__ void put_tile(u16 (*T)[kBK + kLdsPad], uint4 v, int lr, int lk, int lr8, int kk) {
-  if constexpr (MODE == 2) {
-    const u16* pv = (const u16*)&v;
+  __device__ __forceinline__ int koff() const { return MODE == 2 ? kk : lk; }
+  __device__ __forceinline__ void fetch(const G& g, long k, long kend, TapCh tc) {
 #pragma unroll
-    for (int i = 0; i < 8; ++i) T[lr8 + i][kk] = pv[i];
-  } else {
-    *(uint4*)&T[lr][lk] = v;
+    for (int i = 0; i < S; ++i) {
+      uint4 x = make_uint4(0, 0, 0, 0);
+      if constexpr (MODE == 2) {
+        if (ok8[i] && k < kend) x = g.load_rows8(row8[i], tc);
+      } else if constexpr (MODE == 1) {
+        if (ok[i] && k < kend) x = g.load8(r[i], tc);
+      } else {
+        u16* pv = (u16*)&x;
+        TapCh c = tc;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          pv[e] = (ok[i] && k + e < kend) ? g.at(r[i], c) : (u16)0;
+          if (++c.ch == ch) { c.ch = 0; ++c.tap; }
+        }
+      }
+      v[i] = x;
+    }
   }
-}
+  __device__ __forceinline__ void put(u16 (*T)[kBK + kLdsPad]) const {
+#pragma unroll
+    for (int i = 0; i < S; ++i) {
+      if (!mine(i)) continue;
+      if constexpr (MODE == 2) {
+        const u16* pv = (const u16*)&v[i];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) T[lr8 + 64 * i + e][kk] = pv[e];
+      } else {
+        *(uint4*)&T[lr + 64 * i][lk] = v[i];
+      }
+    }
+  }
+};
 
-template <class GA, class GB, class RM, class EP, int AM, int BM>
+template <int TM, int TN, class GA, class GB, class RM, class EP, int AM, int BM>
 __device__ __forceinline__ void gemm_tile(const GA& ga, const GB& gb, const RM& rowmap, const EP& ep, int zi,
                                           long M, long N, long kbeg, long kend, long m0, long n0) {
-  __shared__ __attribute__((aligned(16))) u16 As[kBM][kBK + kLdsPad];
-  __shared__ __attribute__((aligned(16))) u16 Bs[kBN][kBK + kLdsPad];
+  static_assert(TM * TN == 4 * 32 * 32, "four waves of 32 x 32");
+  __shared__ __attribute__((aligned(16))) u16 As[TM][kBK + kLdsPad];
+  __shared__ __attribute__((aligned(16))) u16 Bs[TN][kBK + kLdsPad];
+  constexpr int WN = TN / 32;
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  const int wm = wave >> 1, wn = wave & 1;
+  const int wm = wave / WN, wn = wave % WN;
   f32x4 acc[2][2];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-  // modes 0, 1: row lr, k offset lk (8 consecutive); mode 2: rows lr8 .. lr8 + 7, k offset kk
-  const int lr = t >> 2, lk = (t & 3) * 8;
-  const int kk = t & 31, lr8 = (t >> 5) * 8;
-  const bool am = m0 + lr < M, bn = n0 + lr < N;
-  const bool am8 = m0 + lr8 < M, bn8 = n0 + lr8 < N;
-  const typename GA::Row ra = ga.row(am ? m0 + lr : 0);
-  const typename GB::Row rb = gb.row(bn ? n0 + lr : 0);
-  const int ca = ga.chans(), cb = gb.chans();
+  Stage<GA, AM, TM> sa;
+  Stage<GB, BM, TN> sb;
+  sa.init(ga, m0, M, t);
+  sb.init(gb, n0, N, t);
+  const int ca = sa.ch, cb = sb.ch;
   const int qa = kBK / ca, rma = kBK % ca, qb = kBK / cb, rmb = kBK % cb;
-  // this thread's K offset within a tile, per operand
-  const int oa = AM == 2 ? kk : lk, ob = BM == 2 ? kk : lk;
-  TapCh ta = tapch(kbeg + oa, ca), tb = tapch(kbeg + ob, cb);
-  uint4 va = fetch_tile<GA, AM>(ga, ra, am, am8, m0 + lr8, kbeg + oa, kend, ta, ca);
-  uint4 vb = fetch_tile<GB, BM>(gb, rb, bn, bn8, n0 + lr8, kbeg + ob, kend, tb, cb);
+  TapCh ta = tapch(kbeg + sa.koff(), ca), tb = tapch(kbeg + sb.koff(), cb);
+  sa.fetch(ga, kbeg + sa.koff(), kend, ta);
+  sb.fetch(gb, kbeg + sb.koff(), kend, tb);
   for (long k0 = kbeg; k0 < kend; k0 += kBK) {
-    put_tile<AM>(As, va, lr, lk, lr8, kk);
-    put_tile<BM>(Bs, vb, lr, lk, lr8, kk);
+    sa.put(As);
+    sb.put(Bs);
     __syncthreads();
     if (k0 + kBK < kend) {
       tapch_step(ta, ca, qa, rma);
       tapch_step(tb, cb, qb, rmb);
-      va = fetch_tile<GA, AM>(ga, ra, am, am8, m0 + lr8, k0 + kBK + oa, kend, ta, ca);
-      vb = fetch_tile<GB, BM>(gb, rb, bn, bn8, n0 + lr8, k0 + kBK + ob, kend, tb, cb);
+      sa.fetch(ga, k0 + kBK + sa.koff(), kend, ta);
+      sb.fetch(gb, k0 + kBK + sb.koff(), kend, tb);
     }
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
@@ -374,12 +402,13 @@ __device__ __forceinline__ void gemm_tile(const GA& ga, const GB& gb, const RM& 
 }
 
 // One GEMM, split-K chunk z = blockIdx.z of kchunk K indices.
-template <class GA, class GB, class RM, class EP, int AM, int BM>
+template <int TM, int TN, class GA, class GB, class RM, class EP, int AM, int BM>
 __global__ __launch_bounds__(256) void k_gemm_bf16(GA ga, GB gb, RM rowmap, EP ep, long M, long N, long K,
                                                    long kchunk) {
   const long kbeg = (long)blockIdx.z * kchunk;
-  gemm_tile<GA, GB, RM, EP, AM, BM>(ga, gb, rowmap, ep, (int)blockIdx.z, M, N, kbeg, min(K, kbeg + kchunk),
-                                    (long)blockIdx.x * kBM, (long)blockIdx.y * kBN);
+  gemm_tile<TM, TN, GA, GB, RM, EP, AM, BM>(ga, gb, rowmap, ep, (int)blockIdx.z, M, N, kbeg,
+                                            min(K, kbeg + kchunk), (long)blockIdx.x * TM,
+                                            (long)blockIdx.y * TN);
 }
 
 // Every gather states its vector mode (kMode) and when it applies (vec()).
@@ -395,12 +424,20 @@ static hipError_t gemm_ep(GA ga, GB gb, EP ep, long M, long N, long K, int split
   long kchunk = (K + splits - 1) / splits;
   kchunk = (kchunk + kBK - 1) / kBK * kBK;
   const int z = (int)((K + kchunk - 1) / kchunk);
-  dim3 grid((unsigned)((M + kBM - 1) / kBM), (unsigned)((N + kBN - 1) / kBN), (unsigned)z);
+  const bool narrow = N <= 32;   // 128 x 32 tiles: no MFMA on padding columns
+  const long tm = narrow ? 128 : kBM, tn = narrow ? 32 : kBN;
+  dim3 grid((unsigned)((M + tm - 1) / tm), (unsigned)((N + tn - 1) / tn), (unsigned)z);
   const int am = load_mode(ga), bm = load_mode(gb);
   ScopedTiming _t(tag, s);
-#define WO_GEMM(A_, B_)                                                                              \
-  hipLaunchKernelGGL((k_gemm_bf16<GA, GB, RM, EP, A_, B_>), grid, dim3(256), 0, s, ga, gb, rowmap, ep, M, \
-                     N, K, kchunk)
+#define WO_GEMM(A_, B_)                                                                                  \
+  do {                                                                                                   \
+    if (narrow)                                                                                          \
+      hipLaunchKernelGGL((k_gemm_bf16<128, 32, GA, GB, RM, EP, A_, B_>), grid, dim3(256), 0, s, ga, gb,  \
+                         rowmap, ep, M, N, K, kchunk);                                                   \
+    else                                                                                                 \
+      hipLaunchKernelGGL((k_gemm_bf16<kBM, kBN, GA, GB, RM, EP, A_, B_>), grid, dim3(256), 0, s, ga, gb, \
+                         rowmap, ep, M, N, K, kchunk);                                                   \
+  } while (0)
   if (am && bm) WO_GEMM(GA::kMode, GB::kMode);
   else if (am) WO_GEMM(GA::kMode, 0);
   else if (bm) WO_GEMM(0, GB::kMode);
@@ -423,15 +460,15 @@ struct DgradClasses {
   long M[8], K[8];
 };
 
-template <int AM, int BM>
+template <int TM, int TN, int AM, int BM>
 __global__ __launch_bounds__(256) void k_gemm_dgrad(DgradClasses cl, float* __restrict__ out, long N,
                                                     long Mout) {
   const int c = (int)blockIdx.z;
-  const long m0 = (long)blockIdx.x * kBM;
+  const long m0 = (long)blockIdx.x * TM;
   if (m0 >= cl.M[c]) return;
-  gemm_tile<GatherCol2imClass, GatherWTClass, ClassRows, StoreC, AM, BM>(
+  gemm_tile<TM, TN, GatherCol2imClass, GatherWTClass, ClassRows, StoreC, AM, BM>(
       cl.a[c], cl.b[c], ClassRows{cl.a[c]}, StoreC{out, Mout, N}, 0, cl.M[c], N, 0, cl.K[c], m0,
-      (long)blockIdx.y * kBN);
+      (long)blockIdx.y * TN);
 }
 
 static hipError_t dgrad_classes(const u16* gz, const u16* w, ConvGeom gout, int Cin, int N,
@@ -457,10 +494,18 @@ static hipError_t dgrad_classes(const u16* gz, const u16* w, ConvGeom gout, int 
   if (nc == 0) return hipSuccess;
   const long Mout = (long)N * gout.D * gout.H * gout.W;
   if (Mout >= (1L << 31)) return hipErrorInvalidValue;   // 32-bit position arithmetic
-  dim3 grid((unsigned)((mmax + kBM - 1) / kBM), (unsigned)((Cin + kBN - 1) / kBN), (unsigned)nc);
+  const bool narrow = Cin <= 32;   // 128 x 32 tiles, as in gemm_ep
+  const long tm = narrow ? 128 : kBM, tn = narrow ? 32 : kBN;
+  dim3 grid((unsigned)((mmax + tm - 1) / tm), (unsigned)((Cin + tn - 1) / tn), (unsigned)nc);
   const int am = load_mode(cl.a[0]), bm = load_mode(cl.b[0]);
   ScopedTiming _t("k_gemm_conv_dgrad", s);
-#define WO_DG(A_, B_) hipLaunchKernelGGL((k_gemm_dgrad<A_, B_>), grid, dim3(256), 0, s, cl, out, (long)Cin, Mout)
+#define WO_DG(A_, B_)                                                                                  \
+  do {                                                                                                 \
+    if (narrow)                                                                                        \
+      hipLaunchKernelGGL((k_gemm_dgrad<128, 32, A_, B_>), grid, dim3(256), 0, s, cl, out, (long)Cin, Mout); \
+    else                                                                                               \
+      hipLaunchKernelGGL((k_gemm_dgrad<kBM, kBN, A_, B_>), grid, dim3(256), 0, s, cl, out, (long)Cin, Mout); \
+  } while (0)
   if (am && bm) WO_DG(GatherCol2imClass::kMode, GatherWTClass::kMode);
   else if (am) WO_DG(GatherCol2imClass::kMode, 0);
   else if (bm) WO_DG(0, GatherWTClass::kMode);
@@ -521,6 +566,17 @@ static hipError_t reduce_parts(const float* part, int z, long n, float* out, hip
 
 // ------------------------------------------------------------------ elementwise
 
+// z = z + b[c] (FP32), a = BF16(GELU(z)): the forward epilogue after a split-K
+// sum (StoreBiasGelu's arithmetic).
+__global__ void k_bias_gelu(float* __restrict__ z, const float* __restrict__ b, long P, int Co,
+                            u16* __restrict__ a) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= P * Co) return;
+  const float v = z[i] + b[i % Co];
+  z[i] = v;
+  a[i] = f2bf(gelu_f(v));
+}
+
 // gz = BF16(ga * GELU'(z)) over P positions x Co channels (Co divides 256), and
 // the bias gradient's first stage: workgroup g sums the rounded gz of its rows
 // [g R, g R + R) per channel in a fixed order into part[g][c].  Lanes run along
@@ -534,11 +590,26 @@ __global__ __launch_bounds__(256) void k_gelu_bwd_bias(const float* __restrict__
   const int c = t % Co;
   const long r0 = (long)blockIdx.x * R, r1 = min(P, r0 + R);
   float s = 0.f;
-  for (long p = r0 + t / Co; p < r1; p += step) {
-    const long i = p * Co + c;
-    const u16 b = f2bf(ga[i] * gelu_grad_f(z[i]));
-    gz[i] = b;
-    s += bf2f(b);
+  // four rows per iteration, their loads issued before any is used (the sum
+  // still adds the rows in order)
+  for (long p = r0 + t / Co; p < r1; p += 4 * step) {
+    float gv[4], zv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const long q = p + u * step;
+      const long i = q * Co + c;
+      gv[u] = q < r1 ? ga[i] : 0.f;
+      zv[u] = q < r1 ? z[i] : 0.f;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const long q = p + u * step;
+      if (q < r1) {
+        const u16 b = f2bf(gv[u] * gelu_grad_f(zv[u]));
+        gz[q * Co + c] = b;
+        s += bf2f(b);
+      }
+    }
   }
   red[t] = s;
   __syncthreads();
@@ -758,6 +829,14 @@ static int wgrad_splits(long P, long Co, long K) {
   return (int)std::max<long>(1, std::min<long>({kWgradSplitsMax, P / 256, want}));
 }
 
+// Split-K count of a forward convolution: only when its tiles cannot fill the
+// GPU (fewer than 512), up to 8 chunks of at least 256 K indices.
+static int fwd_splits(long P, long Co, long K) {
+  const long tiles = ((P + kBM - 1) / kBM) * ((Co + kBN - 1) / kBN);
+  if (tiles >= 512) return 1;
+  return (int)std::max<long>(1, std::min<long>({8, (1024 + tiles - 1) / tiles, K / 256}));
+}
+
 static CnnWs cnn_ws(const Net& net) {
   CnnWs w;
   size_t b = 0;
@@ -772,6 +851,8 @@ static CnnWs cnn_ws(const Net& net) {
     maxg = std::max(maxg, L.P_out * L.Cout);
     maxpart = std::max(maxpart, (long)splits_used(L.P_out, wgrad_splits(L.P_out, L.Cout, 27L * L.Cin)) * L.Cout * 27 * L.Cin);
     maxpart = std::max(maxpart, (long)kBiasPartsMax * L.Cout);
+    const long kf = 27L * L.Cin;
+    maxpart = std::max(maxpart, (long)splits_used(kf, fwd_splits(L.P_out, L.Cout, kf)) * L.P_out * L.Cout);
   }
   w.gz = take(maxg * sizeof(u16));
   w.ga = take(maxc * sizeof(float));
@@ -822,10 +903,24 @@ int cnn_run(const float* params, const float* x, int N, int Z, int Y, int X, con
     const long K = 27L * L.Cin;
     float* z = (float*)(w + W.z[l]);
     u16* a = (u16*)(w + W.a[l]);
-    // the GEMM's epilogue adds the bias and applies GELU (z and a written directly)
-    WO_HIP_CHECK(gemm_ep(GatherIm2col{a_in, L.g}, GatherRows{pbf + L.w_off, K, L.Cin},
-                         StoreBiasGelu{z, a, params + L.b_off, L.Cout}, L.P_out, L.Cout, K, 1, s,
-                         "k_gemm_conv_fwd"));
+    const int fs = fwd_splits(L.P_out, L.Cout, K);
+    if (fs == 1) {
+      // the GEMM's epilogue adds the bias and applies GELU (z and a written directly)
+      WO_HIP_CHECK(gemm_ep(GatherIm2col{a_in, L.g}, GatherRows{pbf + L.w_off, K, L.Cin},
+                           StoreBiasGelu{z, a, params + L.b_off, L.Cout}, L.P_out, L.Cout, K, 1, s,
+                           "k_gemm_conv_fwd"));
+    } else {
+      // few tiles: split K, sum the partials in a fixed order into z, then bias and GELU
+      WO_HIP_CHECK(gemm(GatherIm2col{a_in, L.g}, GatherRows{pbf + L.w_off, K, L.Cin}, part, L.P_out, L.Cout,
+                        K, fs, s, "k_gemm_conv_fwd"));
+      { ScopedTiming _tm("k_reduce_parts", s);
+      WO_HIP_CHECK(reduce_parts(part, splits_used(K, fs), L.P_out * L.Cout, z, s));
+      }
+      { ScopedTiming _tm("k_bias_gelu", s);
+      hipLaunchKernelGGL(k_bias_gelu, dim3(blocks(L.P_out * L.Cout, 256)), dim3(256), 0, s, z,
+                         params + L.b_off, L.P_out, L.Cout, a);
+      }
+    }
     a_in = a;
   }
   { ScopedTiming _tm("k_head", s);

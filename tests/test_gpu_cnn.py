@@ -24,7 +24,8 @@ def rel(a, b):
     return float(np.linalg.norm(np.asarray(a, np.float64) - b) / np.linalg.norm(b))
 
 
-SHAPES = [(2, 8, 12, 10, 8, 40), (1, 9, 7, 6, 1, 32), (2, 16, 32, 32, 32, 64)]
+# 64 x 64 and 128 x 32 (N <= 32) tiles, scalar and vector operand loads, ragged edges
+SHAPES = [(2, 8, 12, 10, 8, 40), (1, 9, 7, 6, 1, 32), (2, 16, 32, 32, 32, 64), (1, 6, 10, 14, 24, 16)]
 
 
 @pytest.mark.parametrize("N,D,H,W,Ci,Co", SHAPES)
