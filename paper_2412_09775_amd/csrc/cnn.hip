@@ -84,8 +84,23 @@ struct GatherIm2col {
     const u16* p = ptr(r, t);
     return p ? *p : (u16)0;
   }
+  // the next output position's row (positions in order: w fastest, then h, d, n)
+  __device__ __forceinline__ Row next(Row r) const {
+    r.w0 += 2;
+    if (r.w0 == 2 * g.Wo - 1) {
+      r.w0 = -1;
+      r.h0 += 2;
+      if (r.h0 == 2 * g.Ho - 1) {
+        r.h0 = -1;
+        r.d0 += 2;
+        if (r.d0 == 2 * g.Do - 1) { r.d0 = -1; ++r.n; }
+      }
+    }
+    return r;
+  }
   // 8 consecutive k (channels t.ch .. t.ch + 7 of one tap), when g.C % 8 == 0
   static constexpr int kMode = 1;
+  static constexpr bool kPositions = false;
   __host__ __device__ __forceinline__ bool vec() const { return g.C % 8 == 0; }
   __device__ __forceinline__ uint4 load8(const Row& r, TapCh t) const {
     const u16* p = ptr(r, t);
@@ -103,6 +118,7 @@ struct GatherRows {
   __device__ __forceinline__ int chans() const { return C; }
   __device__ __forceinline__ u16 at(const Row& r, TapCh t) const { return r.p[(long)t.tap * C + t.ch]; }
   static constexpr int kMode = 1;
+  static constexpr bool kPositions = false;
   __host__ __device__ __forceinline__ bool vec() const { return C % 8 == 0; }
   __device__ __forceinline__ uint4 load8(const Row& r, TapCh t) const {
     return *(const uint4*)(r.p + (long)t.tap * C + t.ch);
@@ -149,6 +165,7 @@ struct GatherCol2imClass {
     return p ? *p : (u16)0;
   }
   static constexpr int kMode = 1;
+  static constexpr bool kPositions = false;
   __host__ __device__ __forceinline__ bool vec() const { return g.C % 8 == 0; }
   __device__ __forceinline__ uint4 load8(const Row& r, TapCh t) const {
     const u16* p = ptr(r, t);
@@ -178,6 +195,7 @@ struct GatherWTClass {
   __device__ __forceinline__ u16 at(const Row& r, TapCh t) const { return w[off(t) + r.ci]; }
   // 8 consecutive rows (ci .. ci + 7) at one k, when Cin % 8 == 0
   static constexpr int kMode = 2;
+  static constexpr bool kPositions = false;
   __host__ __device__ __forceinline__ bool vec() const { return Cin % 8 == 0; }
   __device__ __forceinline__ uint4 load_rows8(long n0, TapCh t) const {
     return *(const uint4*)(w + off(t) + n0);
@@ -195,6 +213,7 @@ struct GatherT {
   __device__ __forceinline__ long off(TapCh t) const { return (long)((unsigned long)(unsigned)t.tap * (unsigned)Cout); }
   __device__ __forceinline__ u16 at(const Row& r, TapCh t) const { return gz[off(t) + r.co]; }
   static constexpr int kMode = 2;
+  static constexpr bool kPositions = false;
   __host__ __device__ __forceinline__ bool vec() const { return Cout % 8 == 0; }
   __device__ __forceinline__ uint4 load_rows8(long m0, TapCh t) const {
     return *(const uint4*)(gz + off(t) + m0);
@@ -212,6 +231,20 @@ struct GatherIm2colT {
   }
   // rows n0 .. n0 + 7 (channels of one tap) at position k, when Cin % 8 == 0
   static constexpr int kMode = 2;
+  // K indices are output positions: eight consecutive ones from one decode,
+  // stepping to the next position (no division per element)
+  static constexpr bool kPositions = true;
+  __device__ __forceinline__ uint4 at_run(const Row& r, long k, long kend, bool ok) const {
+    uint4 v = make_uint4(0, 0, 0, 0);
+    u16* pv = (u16*)&v;
+    GatherIm2col::Row p = a.row(ok ? k : 0);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      pv[e] = (ok && k + e < kend) ? a.at(p, TapCh{r.tap, r.ci}) : (u16)0;
+      p = a.next(p);
+    }
+    return v;
+  }
   __host__ __device__ __forceinline__ bool vec() const { return a.g.C % 8 == 0; }
   __device__ __forceinline__ uint4 load_rows8(long n0, TapCh t) const {
     const Row r = row(n0);
@@ -315,6 +348,8 @@ struct Stage {
         if (ok8[i] && k < kend) x = g.load_rows8(row8[i], tc);
       } else if constexpr (MODE == 1) {
         if (ok[i] && k < kend) x = g.load8(r[i], tc);
+      } else if constexpr (G::kPositions) {
+        x = g.at_run(r[i], k, kend, ok[i]);
       } else {
         u16* pv = (u16*)&x;
         TapCh c = tc;
