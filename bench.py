@@ -926,10 +926,10 @@ def restore_section(api, torch, dev, net, ntiles, cnn_iters, ms_iters, graph_mod
         for _ in range(2):   # the second call reuses the graph the first one captured
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            if predict:
-                pred = net.predict(learned_init.network_input(tiles))
+            if predict:   # the library's CNN start (crop, network, denormalisation)
+                pred = api.cnn_init_theta(net.params, nominal, d)
                 theta0 = np.zeros((ntiles, 1, 4))
-                theta0[:, 0, :3] = np.clip(pred, np.array(TUNE_LO[:3]), np.array(TUNE_HI[:3]))
+                theta0[:, 0, :3] = np.clip(pred[:, :3], np.array(TUNE_LO[:3]), np.array(TUNE_HI[:3]))
             out, loss, _, _, f = api.restore_tiles(nominal, d, etas, iters=iters, lr=TUNE_LR, lo=TUNE_LO,
                                                    hi=TUNE_HI, multistart=M, theta0=theta0, nu_c=nucs,
                                                    mask=TUNE_MASK, use_graph=graph_mode,

@@ -485,6 +485,23 @@ int wo_cnn_train_step(float* params, float* adam_m, float* adam_v, int32_t t, do
                       double weight_decay, const float* x, const float* target, int32_t batch,
                       int32_t nz, int32_t ny, int32_t nx, float* y_out, float* loss_out, void* ws,
                       size_t ws_bytes, void* stream);
+/* The prior box the network's outputs are normalised over: output j in
+ * [-1, 1] maps to lo[j] + (y + 1) (hi[j] - lo[j]) / 2 for (defocus um, NA_det,
+ * tilt_zenith rad): lo = (-2, 1.0, 0), hi = (2, 1.3, 30 degrees). */
+void wo_cnn_prior(double lo[3], double hi[3]);
+/* Workspace bytes of wo_cnn_init_theta for n patches (0 if n < 1 or too many). */
+size_t wo_cnn_init_workspace_size(int32_t n);
+/* The learned initialiser as the start of wo_autotune / wo_restore_tiles:
+ * patches packed as for those calls (o[i] their shapes, any nz, ny, nx; d
+ * device), the centred 32 x 64 x 64 window of each (first voxel at
+ * floor((n - 32) / 2), floor((n - 64) / 2) per axis: central planes and
+ * pixels of larger patches, symmetric zero padding of smaller ones) through
+ * the network with parameters params (device, wo_cnn_param_count floats),
+ * denormalised over wo_cnn_prior into theta_out (host [n][4]: defocus, NA_det,
+ * tilt_zenith, and o[i].tilt_azimuth, which the network does not predict) --
+ * the theta0 of a start.  Synchronises `stream` before returning. */
+int wo_cnn_init_theta(const float* params, const wo_optics* o, int32_t n, const float* d, double* theta_out,
+                      void* ws, size_t ws_bytes, void* stream);
 /* Single strided (2) 3x3x3 convolutions with padding 1 on BF16 operands (raw
  * 16-bit storage), channels-last x [N][D][H][W][Cin], weights [Cout][27][Cin]:
  * forward out [N][Do][Ho][Wo][Cout] (no bias), input gradient from

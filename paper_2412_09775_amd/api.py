@@ -43,7 +43,8 @@ SYMBOLS = ("wo_bank_shape", "wo_workspace_size", "wo_transfer_function", "wo_for
            "wo_tile_grid", "wo_stitch_tiles", "wo_timing_select", "wo_midband_loss_grad_aberration",
            "wo_lateral_support", "wo_transfer_function_band",
            "wo_linear_band", "wo_reconstruct_noalloc", "wo_pol5_coupling",
-           "wo_reconstruct_grad_workspace_size", "wo_reconstruct_grad")
+           "wo_reconstruct_grad_workspace_size", "wo_reconstruct_grad", "wo_cnn_prior",
+           "wo_cnn_init_workspace_size", "wo_cnn_init_theta")
 
 _FIELDS = ("model", "nz", "ny", "nx", "dz", "dy", "dx", "wavelength", "na_ill", "na_det",
            "n_medium", "defocus", "tilt_zenith", "tilt_azimuth", "edge_width", "swing")
@@ -163,6 +164,11 @@ def load(path: str = LIB_PATH):
     lib.wo_cnn_gradient.argtypes = [vp, vp, vp, i32, i32, i32, i32, vp, vp, vp, vp, sz, vp]
     lib.wo_cnn_train_step.argtypes = [vp, vp, vp, i32, f64, f64, vp, vp, i32, i32, i32, i32, vp, vp, vp,
                                       sz, vp]
+    lib.wo_cnn_prior.argtypes = [dp, dp]
+    lib.wo_cnn_prior.restype = None
+    lib.wo_cnn_init_workspace_size.argtypes = [i32]
+    lib.wo_cnn_init_workspace_size.restype = sz
+    lib.wo_cnn_init_theta.argtypes = [vp, op, i32, vp, dp, vp, sz, vp]
     conv = [vp, vp, i32, i32, i32, i32, i32, i32, vp]
     lib.wo_conv3d_forward.argtypes = conv + [vp]
     lib.wo_conv3d_input_grad.argtypes = conv + [vp]
@@ -690,6 +696,32 @@ def cnn_workspace(batch, shape, device):
     import torch
     n = int(load().wo_cnn_workspace_size(batch, *shape))
     return torch.empty(n, dtype=torch.uint8, device=device)
+
+
+def cnn_prior():
+    """(lo, hi) of the prior box the network's outputs are normalised over
+    (defocus um, NA_det, tilt_zenith rad)."""
+    import numpy as np
+    lo, hi = (ctypes.c_double * 3)(), (ctypes.c_double * 3)()
+    load().wo_cnn_prior(lo, hi)
+    return np.array(lo[:]), np.array(hi[:])
+
+
+def cnn_init_theta(params, optics, stacks, ws=None, stream=None):
+    """Starting theta (n, 4) of the auto-tune from the network (``wo_cnn_init_theta``):
+    stacks as in pack_stacks, patches of any shape."""
+    import numpy as np
+    import torch
+    lib = load()
+    arr = optics_array(optics)
+    d = pack_stacks(stacks)
+    if ws is None:
+        ws = torch.empty(int(lib.wo_cnn_init_workspace_size(len(arr))), dtype=torch.uint8, device=d.device)
+    out = np.zeros((len(arr), 4))
+    _check(lib.wo_cnn_init_theta(_ptr(params), arr, len(arr), _ptr(d),
+                                 out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), _ptr(ws), ws.numel(),
+                                 _stream(stream)), "wo_cnn_init_theta")
+    return out
 
 
 def cnn_forward(params, x, ws=None, stream=None):

@@ -205,14 +205,24 @@ bool sectors_lit(const wo_optics& oo) {
   source_centre(d, &cy, &cx);
   const double dnu = fmin(1.0 / (oo.nx * oo.dx), 1.0 / (oo.ny * oo.dy));
   const double hw = oo.edge_width * dnu;
+  // S vanishes beyond the tilted source disc widened by the soft edge: only the
+  // rows and columns of its bounding box (one spare frequency pixel) can add
+  // to the sums, in the same order as a scan of the whole grid
+  const double rs = oo.na_ill / oo.wavelength + hw + dnu;
+  std::vector<int> kxs;
+  for (int kx = 0; kx < oo.nx; ++kx)
+    if (fabs(fftfreq(kx, oo.nx, oo.dx) - cx) <= rs) kxs.push_back(kx);
   double bg[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  for (int ky = 0; ky < oo.ny; ++ky)
-    for (int kx = 0; kx < oo.nx; ++kx) {
-      const double fy = fftfreq(ky, oo.ny, oo.dy), fx = fftfreq(kx, oo.nx, oo.dx);
+  for (int ky = 0; ky < oo.ny; ++ky) {
+    const double fy = fftfreq(ky, oo.ny, oo.dy);
+    if (fabs(fy - cy) > rs) continue;
+    for (int kx : kxs) {
+      const double fx = fftfreq(kx, oo.nx, oo.dx);
       const double P = det_pupil(d, da, fy, fx, hw);
       const double S = disc(fy - cy, fx - cx, oo.na_ill / oo.wavelength, hw);
       bg[octant(fy - cy, fx - cx)] += S * P * P;
     }
+  }
   for (double b : bg)
     if (!(b > 0.0)) return false;
   return true;
@@ -672,13 +682,16 @@ double band_count(const wo_optics* o, double nu_c) {
   const double vy = 1.0 / ((double)o->ny * o->dy), vx = 1.0 / ((double)o->nx * o->dx);
   const double rmax = nu_c / 4.0;
   const long my = (long)(rmax / vy) + 1, mx = (long)(rmax / vx) + 1;
+  std::vector<int> sxs;   // the signed columns within the band's reach
+  for (int kx = 0; kx < o->nx; ++kx) {
+    const int sx = kx < (o->nx + 1) / 2 ? kx : kx - o->nx;
+    if (labs((long)sx) <= mx) sxs.push_back(sx);
+  }
   for (int ky = 0; ky < o->ny; ++ky) {
     const int sy = ky < (o->ny + 1) / 2 ? ky : ky - o->ny;
     if (labs((long)sy) > my) continue;
     const double fy = sy * vy;
-    for (int kx = 0; kx < o->nx; ++kx) {
-      const int sx = kx < (o->nx + 1) / 2 ? kx : kx - o->nx;
-      if (labs((long)sx) > mx) continue;
+    for (int sx : sxs) {
       const double fx = sx * vx;
       const double r = sqrt(fy * fy + fx * fx);
       if (r >= nu_c / 8.0 && r <= nu_c / 4.0) ++cnt;

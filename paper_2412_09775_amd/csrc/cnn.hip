@@ -1120,6 +1120,52 @@ __global__ void k_crop(const float* __restrict__ in, int nz, int ny, int nx, flo
   out[e] = in_win ? in[((i * nz + zi) * (long)ny + yi) * nx + xi] : 0.f;
 }
 
+// Centred network windows of packed patches of uneven shapes: record j of a
+// launch gives patch j's offset in the packed stacks and its shape; the
+// window's first voxel sits at floor((n - o) / 2) along each axis (central
+// planes of deeper patches, symmetric zero padding of shallower ones).
+struct CropRec {
+  long off;
+  int nz, ny, nx;
+};
+constexpr int kCropRecs = 16;
+struct CropBatch {
+  CropRec r[kCropRecs];
+};
+__device__ __forceinline__ int floor_half(int v) { return v >= 0 ? v / 2 : -((1 - v) / 2); }
+__global__ void k_crop_packed(const float* __restrict__ in, CropBatch b, int nrec, float* __restrict__ out,
+                              int oz, int oy, int ox) {
+  const long per = (long)oz * oy * ox;
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nrec * per) return;
+  const int j = (int)(e / per);
+  const long w = e - j * per;
+  const int x = (int)(w % ox), y = (int)((w / ox) % oy), z = (int)(w / ((long)ox * oy));
+  const CropRec c = b.r[j];
+  const int zi = z + floor_half(c.nz - oz), yi = y + floor_half(c.ny - oy), xi = x + floor_half(c.nx - ox);
+  const bool in_win = zi >= 0 && zi < c.nz && yi >= 0 && yi < c.ny && xi >= 0 && xi < c.nx;
+  out[e] = in_win ? in[c.off + ((long)zi * c.ny + yi) * c.nx + xi] : 0.f;
+}
+
+// The learned initialiser's prior box (normalised outputs -1 .. 1 span it).
+constexpr double kPriorLo[3] = {-2.0, 1.0, 0.0};
+constexpr double kPriorHi[3] = {2.0, 1.3, 0.52359877559829887};   // 30 degrees
+constexpr int kNetZ = 32, kNetY = 64, kNetX = 64;
+
+struct CnnInitWs {
+  size_t x, net, y, total;
+};
+static CnnInitWs cnn_init_ws(int n) {
+  CnnInitWs w;
+  size_t b = 0;
+  auto take = [&](size_t bytes) { size_t o = b; b += al(bytes); return o; };
+  w.x = take((size_t)n * kNetZ * kNetY * kNetX * sizeof(float));
+  w.net = take(cnn_workspace_size(n, kNetZ, kNetY, kNetX));
+  w.y = take((size_t)n * kCnnOut * sizeof(float));
+  w.total = b;
+  return w;
+}
+
 }  // namespace wo
 
 // ------------------------------------------------------------------ C ABI
@@ -1157,6 +1203,60 @@ int wo_crop_stacks(const float* in, int32_t n, int32_t nz, int32_t ny, int32_t n
   hipLaunchKernelGGL(wo::k_crop, dim3(wo::blocks(total, 256)), dim3(256), 0, (hipStream_t)stream, in,
                      nz, ny, nx, out, oz, oy, ox, z0, y0, x0, keep_z, total);
   WO_HIP_CHECK(hipGetLastError());
+  return WO_OK;
+}
+
+void wo_cnn_prior(double lo[3], double hi[3]) {
+  for (int j = 0; j < 3; ++j) {
+    lo[j] = wo::kPriorLo[j];
+    hi[j] = wo::kPriorHi[j];
+  }
+}
+
+size_t wo_cnn_init_workspace_size(int32_t n) {
+  if (n < 1 || (long)n * wo::kNetZ * wo::kNetY * wo::kNetX >= (1L << 31)) return 0;
+  return wo::cnn_init_ws(n).total;
+}
+
+int wo_cnn_init_theta(const float* params, const wo_optics* o, int32_t n, const float* d, double* theta_out,
+                      void* ws, size_t ws_bytes, void* stream) {
+  if (!params || !o || !d || !theta_out || !ws || n < 1) return WO_EINVAL;
+  const size_t need = wo_cnn_init_workspace_size(n);
+  if (need == 0) return WO_EINVAL;
+  if (ws_bytes < need) return WO_ENOMEM;
+  for (int i = 0; i < n; ++i)
+    if (o[i].nz < 1 || o[i].ny < 1 || o[i].nx < 1) return WO_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  const wo::CnnInitWs W = wo::cnn_init_ws(n);
+  char* w = (char*)ws;
+  float* x = (float*)(w + W.x);
+  float* y = (float*)(w + W.y);
+  const long per = (long)wo::kNetZ * wo::kNetY * wo::kNetX;
+  long off = 0;
+  for (int i0 = 0; i0 < n; i0 += wo::kCropRecs) {
+    const int nr = std::min(wo::kCropRecs, n - i0);
+    wo::CropBatch b{};
+    for (int j = 0; j < nr; ++j) {
+      const wo_optics& oi = o[i0 + j];
+      b.r[j] = wo::CropRec{off, oi.nz, oi.ny, oi.nx};
+      off += (long)oi.nz * oi.ny * oi.nx;
+    }
+    hipLaunchKernelGGL(wo::k_crop_packed, dim3(wo::blocks(nr * per, 256)), dim3(256), 0, s, d, b, nr,
+                       x + (long)i0 * per, wo::kNetZ, wo::kNetY, wo::kNetX);
+    WO_HIP_CHECK(hipGetLastError());
+  }
+  const int r = wo::cnn_run(params, x, n, wo::kNetZ, wo::kNetY, wo::kNetX, nullptr, y, nullptr, nullptr,
+                            w + W.net, s);
+  if (r) return r;
+  std::vector<float> h((size_t)n * wo::kCnnOut);
+  WO_HIP_CHECK(hipMemcpyAsync(h.data(), y, h.size() * sizeof(float), hipMemcpyDeviceToHost, s));
+  WO_HIP_CHECK(hipStreamSynchronize(s));
+  for (int i = 0; i < n; ++i) {
+    for (int j = 0; j < 3; ++j)
+      theta_out[4 * i + j] = wo::kPriorLo[j] + 0.5 * ((double)h[(size_t)wo::kCnnOut * i + j] + 1.0) *
+                                                    (wo::kPriorHi[j] - wo::kPriorLo[j]);
+    theta_out[4 * i + 3] = o[i].tilt_azimuth;
+  }
   return WO_OK;
 }
 

@@ -49,11 +49,10 @@ def restore_fov(stack, template, grid=(6, 6), overlap=(0, 0), eta=1e-2, net=None
     th0 = None
     if theta0 is not None:
         th0 = np.asarray(theta0, dtype=np.float64).reshape(n, 1, 4)
-    elif net is not None:
-        from . import learned_init
-        pred = net.predict(learned_init.network_input(list(tiles)))
+    elif net is not None:   # the library's CNN start (centre windows, network, prior)
+        pred = api.cnn_init_theta(net.params, opts, tiles)
         th0 = np.zeros((n, 1, 4))
-        th0[:, 0, :3] = np.clip(pred, np.asarray(lo[:3]), np.asarray(hi[:3]))
+        th0[:, 0, :3] = np.clip(pred[:, :3], np.asarray(lo[:3]), np.asarray(hi[:3]))
         th0[:, 0, 3] = template.tilt_azimuth
     out, loss, _, _, f = api.restore_tiles(opts, tiles, np.broadcast_to(eta, (n,)), iters=iters, lr=lr,
                                            lo=lo, hi=hi, mask=mask, theta0=th0, nu_c=nu_c,

@@ -199,3 +199,21 @@ def test_pol5_coupling_is_the_oracle_coupling_in_fp32(lib):
         for g, r in ((got.real, ref.real), (got.imag, ref.imag)):
             assert np.all(np.abs(g - r) <= 2.0 ** -24 * np.abs(r) + 1e-15)
     assert lib.wo_pol5_coupling(float("nan"), None) == -1
+
+
+def test_cnn_start_validates_on_the_host_and_shares_the_prior(lib):
+    """wo_cnn_prior is learned_init's prior box; wo_cnn_init_theta rejects bad
+    arguments before any GPU work (fake pointers never touched)."""
+    import numpy as np
+    from paper_2412_09775_amd import learned_init
+    lo, hi = api.cnn_prior()
+    assert np.array_equal(lo, learned_init.PRIOR_LO) and np.array_equal(hi, learned_init.PRIOR_HI)
+    assert lib.wo_cnn_init_workspace_size(0) == 0
+    need = lib.wo_cnn_init_workspace_size(3)
+    assert need > 3 * 32 * 64 * 64 * 4
+    one = ctypes.c_void_p(1)
+    arr = api.optics_array([_optics()] * 3)
+    out = (ctypes.c_double * 12)()
+    assert lib.wo_cnn_init_theta(None, arr, 3, one, out, one, need, None) == -1
+    assert lib.wo_cnn_init_theta(one, arr, 0, one, out, one, need, None) == -1
+    assert lib.wo_cnn_init_theta(one, arr, 3, one, out, one, need - 1, None) == -3

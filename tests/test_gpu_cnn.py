@@ -201,3 +201,26 @@ def test_trained_network_gains_over_the_start_without_it(gpu_lib):
         errs[label] = float(np.median(np.maximum(e[:, 0], e[:, 2])))
     print(f"  after 20 iterations, median max(defocus, tilt) error: {errs}")
     assert errs["cnn"] < 0.5 * errs["centre"]
+
+
+def test_cnn_start_call_equals_the_python_path(gpu_lib):
+    """wo_cnn_init_theta (crop of packed uneven patches, network, denormalisation
+    in the library) gives exactly what learned_init's network_input + cnn_forward +
+    denormalise_theta give, for patches deeper and shallower, wider and narrower
+    (odd sizes: floor offsets) than the network input."""
+    import torch
+    from paper_2412_09775_amd import learned_init
+    shapes = [(16, 128, 192), (17, 63, 65), (48, 64, 64), (33, 200, 90), (32, 64, 64), (5, 31, 129)]
+    rng = np.random.default_rng(77)
+    tiles = [torch.from_numpy(rng.standard_normal(s).astype(np.float32)).cuda() for s in shapes]
+    opts = [gpu_lib.Optics(model=2, nz=s[0], ny=s[1], nx=s[2], dz=0.2, dy=0.1, dx=0.1, wavelength=0.532,
+                           na_ill=0.5, na_det=1.15, n_medium=1.33, tilt_azimuth=0.1 * i)
+            for i, s in enumerate(shapes)]
+    net = learned_init.LearnedInit("cuda", seed=3)
+    print("[case] cnn start call vs python path", flush=True)
+    got = gpu_lib.cnn_init_theta(net.params, opts, tiles)
+    x = learned_init.network_input(tiles)
+    y = gpu_lib.cnn_forward(net.params, x).cpu().numpy()
+    ref = learned_init.denormalise_theta(y.astype(np.float64))
+    assert np.array_equal(got[:, :3], ref)
+    assert np.array_equal(got[:, 3], [o.tilt_azimuth for o in opts])
