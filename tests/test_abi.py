@@ -217,3 +217,27 @@ def test_cnn_start_validates_on_the_host_and_shares_the_prior(lib):
     assert lib.wo_cnn_init_theta(None, arr, 3, one, out, one, need, None) == -1
     assert lib.wo_cnn_init_theta(one, arr, 0, one, out, one, need, None) == -1
     assert lib.wo_cnn_init_theta(one, arr, 3, one, out, one, need - 1, None) == -3
+
+
+def test_nine_aperture_validity_is_the_oracles_lit_criterion(lib):
+    """The 9-aperture model needs light in every sector: sum S_c P^2 > 0 for c < 8
+    (oracle pupils).  The library checks it on the host (scanning only the source
+    disc's bounding box); wo_lateral_support reports it (WO_EINVAL when unlit)."""
+    import numpy as np
+    from oracle import optics as op
+    cases = [dict(na_ill=0.5), dict(na_ill=0.05), dict(na_ill=0.12, tilt_zenith=0.3, tilt_azimuth=0.7),
+             dict(na_ill=0.4, det_tilt=0.25, det_azimuth=-0.6, na_det=0.9), dict(na_ill=0.02, edge_width=0.5)]
+    seen = set()
+    for kw in cases:
+        base = dict(model=op.SECTORS9_3D, nz=8, ny=64, nx=48, dz=0.2, dy=0.1, dx=0.1, wavelength=0.532,
+                    na_ill=0.5, na_det=1.2, n_medium=1.33)
+        base.update(kw)
+        oo = op.Optics(**base)
+        P = op.detection_pupil(oo)
+        lit = all(np.sum(op.sector_pupil(oo, c) * P * P) > 0 for c in range(8))
+        ao = api.Optics(**{k: v for k, v in base.items()})
+        out = api.WoSupport()
+        st = lib.wo_lateral_support(api.optics_array([ao]), 1, ctypes.byref(out))
+        assert (st == 0) == lit, (kw, st, lit)
+        seen.add(lit)
+    assert seen == {True, False}
