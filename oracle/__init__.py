@@ -14,6 +14,9 @@ against the paper:
 * ``tf``       -- transfer functions as autocorrelations of pupils (Table 1,
                   scalar column), the 5-channel polarisation bank, the thin
                   (phase-from-defocus) model.
+* ``vector``   -- the vector label-free bank (Table 1, vector column): tensor
+                  pupils, the Green's tensor spectrum, spherical-harmonic
+                  object tensors and Stokes / analyser channels.
 * ``linear``   -- forward model D = sum_p H_cp F_p + b delta (Methods, "Linear
                   contrast-separable shift-invariant imaging systems"),
                   Tikhonov reconstruction (Methods, "Reconstruction
@@ -37,4 +40,4 @@ value printed in the paper (parity unpinned; judged against synthetic ground
 truth only).
 """
 
-from . import optics, tf, linear, autotune, cnn, stitch  # noqa: F401
+from . import optics, tf, vector, linear, autotune, cnn, stitch  # noqa: F401

@@ -60,6 +60,7 @@ LABELFREE_3D = 1
 LABELFREE_THIN = 2
 POL5_3D = 3
 SECTORS9_3D = 4
+VECTOR_3D = 5
 
 
 @dataclasses.dataclass
@@ -85,6 +86,12 @@ class Optics:
     zernike: tuple = ()        # detection aberration, waves, Noll j = 5, 6, ... (R18)
     det_tilt: float = 0.0      # detection axis zenith angle, rad (R20)
     det_azimuth: float = 0.0   # and its azimuth, rad
+    # vector label-free model only (R21-R26, oracle.vector): channel set (0: Stokes
+    # S0..S3 under the illumination Jones state ill_jones; 1: the five swing states
+    # through the circular analyser) and property codes 2 b + part
+    vec_channels: int = 0
+    vec_props: tuple = (0, 16, 8, 1)
+    ill_jones: tuple = (2 ** -0.5, 1j * 2 ** -0.5)
 
     def replace(self, **kw) -> "Optics":
         return dataclasses.replace(self, **kw)
@@ -327,6 +334,8 @@ def check_optics(o: Optics) -> None:
         raise ValueError("detection pupil reaches the evanescent boundary")
     if o.det_tilt != 0.0 and any(o.zernike):
         raise ValueError("detection tilt with aberrations is not supported (R20)")
+    if o.model == VECTOR_3D and o.det_tilt != 0.0:
+        raise ValueError("the vector model's pupil mapping is for the untilted objective (R24)")
     qy, qx = source_centre(o)
     q0 = math.hypot(qy, qx)
     if o.model != FLUOR_3D and o.na_ill / o.wavelength + q0 + hw >= km:

@@ -180,6 +180,9 @@ def transfer_function(o: op.Optics) -> np.ndarray:
         return pol5_3d(o)
     if o.model == op.SECTORS9_3D:
         return sectors9_3d(o)
+    if o.model == op.VECTOR_3D:
+        from . import vector
+        return vector.vector_3d(o)
     raise ValueError(f"unknown model {o.model}")
 
 
@@ -195,6 +198,8 @@ def bank_shape(o: op.Optics):
         return 5, 4, 3
     if o.model == op.SECTORS9_3D:
         return 9, 1, 3
+    if o.model == op.VECTOR_3D:
+        return (4 if o.vec_channels == 0 else 5), len(o.vec_props), 3
     raise ValueError(o.model)
 
 
