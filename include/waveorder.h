@@ -55,6 +55,10 @@
  *                   are relative to its own background (Results,
  *                   cardiomyocytes; Methods "Cardiomyocyte reconstructions";
  *                   Fig. 4c's 9 x 1 column)
+ *   VECTOR_3D       C x P, 3D  vector (non-paraxial) label-free bank (Table 1,
+ *                   vector column): C = 4 Stokes channels or the 5 swing
+ *                   states, P = vec_nprops spherical-harmonic coefficients
+ *                   (see the vec_* fields of wo_optics)
  */
 #ifndef WAVEORDER_H
 #define WAVEORDER_H
@@ -82,7 +86,8 @@ enum {
   WO_MODEL_LABELFREE_3D = 1,
   WO_MODEL_LABELFREE_THIN = 2,
   WO_MODEL_POL5_3D = 3,
-  WO_MODEL_SECTORS9_3D = 4
+  WO_MODEL_SECTORS9_3D = 4,
+  WO_MODEL_VECTOR_3D = 5
 };
 
 enum {
@@ -129,6 +134,30 @@ typedef struct wo_optics {
      (WO_EUNSUPPORTED).  The data stay on the sample grid. */
   double det_tilt;
   double det_azimuth;
+  /* Vector label-free model (WO_MODEL_VECTOR_3D; Table 1, vector column,
+     label-free row; Methods "Physically interpretable basis functions").  The
+     source point q of the disc illuminates with the plane wave of
+     polarisation e(q) = Q(q) J, J the Jones vector in the condenser pupil and
+     Q(q) = t^ r^T + f^ f^_t^T the aplanatic map of the pupil's radial and
+     azimuthal directions onto the wave's polar and azimuthal unit vectors;
+     the detection pupil tensor is P E Q^T and the Green's tensor spectrum
+     (I - k^ k^T) g.  Channels (vec_channels): 0 the four Stokes parameters
+     S0..S3 of the detected field (analysers I, diag(1, -1), [[0, 1], [1, 0]],
+     [[0, -i], [i, 0]]) under the Jones state ill_jones; 1 the five swing
+     states of POL5_3D through its circular analyser.  Properties: vec_nprops
+     (1..8) real coefficients, property k of the tensor Y_b (vec_props[k] =
+     2 b) or i Y_b (2 b + 1) with the spherical-harmonic tensors b = 0 the
+     identity (phase; its imaginary coefficient absorption), 1..3 the
+     antisymmetric (yz - zy)/2, (zx - xz)/2, (xy - yx)/2, 4..8 the symmetric
+     traceless (xy + yx)/2, (yz + zy)/2, (2zz - xx - yy)/(2 sqrt 3),
+     (xz + zx)/2, (xx - yy)/2.  Data are E^H M_c E / I_bg with the channel
+     background J^H M_c J.  Every patch of a call has the same channels and
+     properties.  Not combined with det_tilt (WO_EUNSUPPORTED).  The linear
+     calls take vec_nprops 1, 2 or 4.  Other models ignore these fields. */
+  int32_t vec_channels;
+  int32_t vec_nprops;
+  int32_t vec_props[8];
+  double ill_jones[4];     /* re Jx, im Jx, re Jy, im Jy */
 } wo_optics;
 
 /* Bank shape of the model: *C channels, *P properties, *dims spatial
@@ -140,7 +169,12 @@ int wo_bank_shape(const wo_optics* o, int32_t* C, int32_t* P, int32_t* dims, int
 size_t wo_workspace_size(const wo_optics* o, int32_t n, int32_t op);
 
 /* Transfer-function bank (Table 1, scalar column; the polarisation bank is
- * the paraxial Jones reduction H_cp = Re(kappa_cp) H_phase + Im(kappa_cp) H_abs).
+ * the paraxial Jones reduction H_cp = Re(kappa_cp) H_phase + Im(kappa_cp) H_abs;
+ * WO_MODEL_VECTOR_3D the vector column: H_cp = FFT3(2 Re R_cp) with the
+ * first-order channel response R_cp = 1/(Y X I_bg) sum M_c^{ii'} conj(v_ik)
+ * u_i'n T_p^{nk} of the detected scattered fields u = IFFT2[P_i'j G_jn prop]
+ * and the detected direct fields times the conjugate incident field
+ * v = IFFT2[S P_ik' e_k' conj(e_k) prop], computed on the full lateral grid).
  * tf_out: complex64 [n][C][P][nz][ny][Xh] (3D) or [n][nz][2][ny][Xh] (thin).
  * WO_EINVAL if a pupil reaches the evanescent boundary n/lambda0 or an NA,
  * size or wavelength is not positive; WO_EALIAS if the lateral support

@@ -206,3 +206,41 @@ def vector_3d(o: op.Optics, paraxial: bool = False) -> np.ndarray:
         for p, T in enumerate(props):
             out[c, p] = sfft.fftn(2.0 * point_response(o, J, M, T, paraxial).real)
     return out
+
+
+def vector_3d_at(o: op.Optics, kz: int, ky: int, kx: int) -> np.ndarray:
+    """(C, P) bank at one frequency index by the direct sum over source points q
+    (no FFT): the lateral spectrum of R_cp at nu is
+        C_cp(nu, z) = (1 / I_bg) sum_q sum M_c^{ii'} conj(V_ik(q)) U_i'n(q + nu) T_p^{nk}
+    with V = S (P e)_i conj(e_k) prop and U = P_i'j G_jn prop (the correlation
+    theorem applied to R26), and H_cp = sum_z e^{-i 2 pi kz z / Z}
+    (C_cp(nu, z) + conj(C_cp(-nu, z)))."""
+    S = op.illumination_pupil(o)
+    Pt = detection_tensor(o)
+    G = greens_tensor(o)
+    ibg = op.background(o)
+    chans = channels(o)
+    props = [property_tensor(c) for c in o.vec_props]
+    PG = np.einsum("yxij,yxjn->yxin", Pt, G)
+    qy, qx = np.nonzero(S * op.detection_pupil(o))
+    kzz = op.axial_wavenumber(o)
+    zs = op.z_planes_3d(o) - o.defocus
+
+    def lateral(c, J, M, T, ny_, nx_):
+        e = incident_field(o, J)
+        Pe = np.einsum("yxij,yxj->yxi", Pt, e)
+        py, px = (qy + ny_) % o.ny, (qx + nx_) % o.nx
+        V = S[qy, qx, None, None] * Pe[qy, qx, :, None] * np.conj(e[qy, qx, None, :])   # (q, i, k)
+        U = PG[py, px]                                                                   # (q, i', n)
+        w = np.einsum("ab,qak,qbn,nk->q", M, np.conj(V), U, T)
+        dk = kzz[py, px] - kzz[qy, qx]
+        return np.exp(2j * np.pi * np.outer(zs, dk)) @ w / ibg                          # (Z,)
+
+    ez = np.exp(-2j * np.pi * kz * np.arange(o.nz) / o.nz)
+    out = np.empty((len(chans), len(props)), dtype=np.complex128)
+    for c, (J, M) in enumerate(chans):
+        for p, T in enumerate(props):
+            cp = lateral(c, J, M, T, ky, kx)
+            cm = lateral(c, J, M, T, (-ky) % o.ny, (-kx) % o.nx)
+            out[c, p] = np.sum(ez * (cp + np.conj(cm)))
+    return out

@@ -24,6 +24,7 @@ MODEL_LABELFREE_3D = 1
 MODEL_LABELFREE_THIN = 2
 MODEL_POL5_3D = 3
 MODEL_SECTORS9_3D = 4
+MODEL_VECTOR_3D = 5
 
 OP_TRANSFER_FUNCTION = 0
 OP_FORWARD = 1
@@ -57,7 +58,9 @@ class WoOptics(ctypes.Structure):
     _fields_ = ([("model", ctypes.c_int32), ("nz", ctypes.c_int32), ("ny", ctypes.c_int32),
                  ("nx", ctypes.c_int32)] + [(f, ctypes.c_double) for f in _FIELDS[4:]]
                 + [("zernike", ctypes.c_double * N_ZERNIKE)]
-                + [("det_tilt", ctypes.c_double), ("det_azimuth", ctypes.c_double)])
+                + [("det_tilt", ctypes.c_double), ("det_azimuth", ctypes.c_double)]
+                + [("vec_channels", ctypes.c_int32), ("vec_nprops", ctypes.c_int32),
+                   ("vec_props", ctypes.c_int32 * 8), ("ill_jones", ctypes.c_double * 4)])
 
 
 @dataclasses.dataclass
@@ -83,6 +86,11 @@ class Optics:
     zernike: tuple = ()   # detection aberration, waves, Noll j = 5..11 (up to 7 values)
     det_tilt: float = 0.0       # oblique detection: detection axis zenith, rad
     det_azimuth: float = 0.0    # and azimuth, rad
+    # vector model (MODEL_VECTOR_3D): channel set (0 Stokes S0..S3 under ill_jones,
+    # 1 the five swing states), property codes 2 b + part (up to 8), Jones vector
+    vec_channels: int = 0
+    vec_props: tuple = (0, 16, 8, 1)
+    ill_jones: tuple = (2 ** -0.5, 1j * 2 ** -0.5)
 
 
 class WoAutotuneOpts(ctypes.Structure):
@@ -216,6 +224,20 @@ def optics_array(optics) -> ctypes.Array:
         for f in ("det_tilt", "det_azimuth"):
             v = o.get(f, 0.0) if isinstance(o, dict) else getattr(o, f, 0.0)
             setattr(arr[i], f, float(v))
+
+        def opt(f, default):
+            return o.get(f, default) if isinstance(o, dict) else getattr(o, f, default)
+
+        arr[i].vec_channels = int(opt("vec_channels", 0))
+        props = tuple(int(p) for p in opt("vec_props", (0, 16, 8, 1)))
+        if len(props) > 8:
+            raise ValueError("at most 8 vector-model properties")
+        arr[i].vec_nprops = len(props)
+        for k in range(8):
+            arr[i].vec_props[k] = props[k] if k < len(props) else 0
+        jx, jy = (complex(v) for v in opt("ill_jones", (2 ** -0.5, 1j * 2 ** -0.5)))
+        for k, v in enumerate((jx.real, jx.imag, jy.real, jy.imag)):
+            arr[i].ill_jones[k] = v
     return arr
 
 

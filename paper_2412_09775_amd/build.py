@@ -17,7 +17,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libwaveorder.so")
-SOURCES = ["fft.hip", "tf.hip", "autotune.hip", "cnn.hip", "plans.hip", "stitch.hip", "api.hip"]
+SOURCES = ["fft.hip", "tf.hip", "vector.hip", "autotune.hip", "cnn.hip", "plans.hip", "stitch.hip", "api.hip"]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -99,6 +99,7 @@ bool smooth235(int n) {
 struct Shape {
   int C, P, dims;
   bool thin;
+  bool pol5 = false;   // the polarisation model (its bank has a reduced form)
   long Z, Y, X, Xh;
 };
 
@@ -115,8 +116,15 @@ bool bank_shape(const wo_optics* o, Shape* s) {
     case WO_MODEL_LABELFREE_THIN: s->C = o->nz; s->P = 2; s->thin = true; s->dims = 2; break;
     case WO_MODEL_POL5_3D: s->C = 5; s->P = 4; break;
     case WO_MODEL_SECTORS9_3D: s->C = 9; s->P = 1; break;
+    case WO_MODEL_VECTOR_3D:
+      if (o->vec_channels != 0 && o->vec_channels != 1) return false;
+      if (o->vec_nprops < 1 || o->vec_nprops > 8) return false;
+      s->C = o->vec_channels == 0 ? 4 : 5;
+      s->P = o->vec_nprops;
+      break;
     default: return false;
   }
+  s->pol5 = o->model == WO_MODEL_POL5_3D;
   return true;
 }
 
@@ -126,7 +134,13 @@ long bank_elems(const Shape& s) {
 
 int check_sampling(const wo_optics* o) {
   if (!o) return WO_EINVAL;
-  if (o->model < 0 || o->model > 4) return WO_EINVAL;
+  if (o->model < 0 || o->model > 5) return WO_EINVAL;
+  if (o->model == WO_MODEL_VECTOR_3D) {
+    if ((o->vec_channels != 0 && o->vec_channels != 1) || o->vec_nprops < 1 || o->vec_nprops > 8)
+      return WO_EINVAL;
+    for (int k = 0; k < o->vec_nprops; ++k)
+      if (o->vec_props[k] < 0 || o->vec_props[k] > 17) return WO_EINVAL;
+  }
   if (!(o->dz > 0 && o->dy > 0 && o->dx > 0 && o->wavelength > 0)) return WO_EINVAL;
   if (!smooth235(o->nz) || !smooth235(o->ny) || !smooth235(o->nx)) return WO_EUNSUPPORTED;
   if (o->nx % 2 || o->ny % 2) return WO_EUNSUPPORTED;
@@ -135,8 +149,14 @@ int check_sampling(const wo_optics* o) {
 }
 
 bool same_sampling(const wo_optics* a, const wo_optics* b) {
-  return a->model == b->model && a->nz == b->nz && a->ny == b->ny && a->nx == b->nx &&
-         a->dz == b->dz && a->dy == b->dy && a->dx == b->dx;
+  if (!(a->model == b->model && a->nz == b->nz && a->ny == b->ny && a->nx == b->nx &&
+        a->dz == b->dz && a->dy == b->dy && a->dx == b->dx))
+    return false;
+  if (a->model != WO_MODEL_VECTOR_3D) return true;
+  if (a->vec_channels != b->vec_channels || a->vec_nprops != b->vec_nprops) return false;
+  for (int k = 0; k < a->vec_nprops && k < 8; ++k)
+    if (a->vec_props[k] != b->vec_props[k]) return false;
+  return true;
 }
 
 // Validity of the sampled model (same conditions as the FP64 oracle).
@@ -175,7 +195,13 @@ int check_optics(const wo_optics* o) {
   ax = km - sqrt(km * km - kd * kd);
   if (lat >= nyq) return WO_EALIAS;
   if (o->model != WO_MODEL_LABELFREE_THIN && ax >= 0.5 / o->dz) return WO_EALIAS;
-  if (o->model == WO_MODEL_POL5_3D && !(isfinite(o->swing))) return WO_EINVAL;
+  if ((o->model == WO_MODEL_POL5_3D || o->model == WO_MODEL_VECTOR_3D) && !(isfinite(o->swing)))
+    return WO_EINVAL;
+  if (o->model == WO_MODEL_VECTOR_3D) {
+    if (o->det_tilt != 0.0) return WO_EUNSUPPORTED;   // the pupil map is the untilted objective's
+    for (int j = 0; j < 4; ++j)
+      if (!isfinite(o->ill_jones[j])) return WO_EINVAL;
+  }
   for (int j = 0; j < 7; ++j)
     if (!isfinite(o->zernike[j])) return WO_EINVAL;
   return WO_OK;
@@ -242,12 +268,14 @@ int validate(const wo_optics* o, int32_t n) {
 }
 
 // Polarisation coupling kappa_cp = conj(a^H e_c) (a^H B_p e_c), FP64 on the host.
-void pol5_kappa(double swing, double out[5][4][2]) {
-  typedef std::complex<double> cd;
+typedef std::complex<double> cd;
+
+// The five illumination states of the swing: e_0 = (1, i)/sqrt2 and
+// e_c = J(2 pi swing, alpha_c) e_0, alpha_c in {0, pi/4, pi/2, 3 pi/4}.
+void pol5_states(double swing, cd states[5][2]) {
   const double r2 = 1.0 / sqrt(2.0);
   const cd I(0.0, 1.0);
   cd e0[2] = {cd(r2, 0), cd(0, r2)};
-  cd states[5][2];
   states[0][0] = e0[0];
   states[0][1] = e0[1];
   const double delta = 2.0 * M_PI * swing;
@@ -262,6 +290,13 @@ void pol5_kappa(double swing, double out[5][4][2]) {
     states[s + 1][0] = c * v0 - sn * v1;
     states[s + 1][1] = sn * v0 + c * v1;
   }
+}
+
+void pol5_kappa(double swing, double out[5][4][2]) {
+  const double r2 = 1.0 / sqrt(2.0);
+  const cd I(0.0, 1.0);
+  cd states[5][2];
+  pol5_states(swing, states);
   const cd ah[2] = {cd(r2, 0), cd(0, r2)};  // a^H for a = (1, -i)/sqrt2
   const cd B[4][2][2] = {
       {{1.0, 0.0}, {0.0, 1.0}},
@@ -309,7 +344,124 @@ Coupling coupling_of(double swing) {
   return c;
 }
 
-bool is_pol5(const Shape& s) { return !s.thin && s.C == 5 && s.P == 4; }
+bool is_pol5(const Shape& s) { return s.pol5; }
+
+// Spherical-harmonic tensor Y_b of the vector model in (x, y, z), entry 3 n + k:
+// b = 0 the identity, 1..3 (yz - zy)/2, (zx - xz)/2, (xy - yx)/2, 4..8
+// (xy + yx)/2, (yz + zy)/2, (2zz - xx - yy)/(2 sqrt 3), (xz + zx)/2, (xx - yy)/2.
+void sh_tensor(int b, double T[9]) {
+  for (int e = 0; e < 9; ++e) T[e] = 0.0;
+  auto sym = [&](int a, int c) { T[3 * a + c] += 0.5; T[3 * c + a] += 0.5; };
+  auto asym = [&](int a, int c) { T[3 * a + c] += 0.5; T[3 * c + a] -= 0.5; };
+  switch (b) {
+    case 0: T[0] = T[4] = T[8] = 1.0; break;
+    case 1: asym(1, 2); break;
+    case 2: asym(2, 0); break;
+    case 3: asym(0, 1); break;
+    case 4: sym(0, 1); break;
+    case 5: sym(1, 2); break;
+    case 6: {
+      const double r = 1.0 / (2.0 * sqrt(3.0));
+      T[0] = -r;
+      T[4] = -r;
+      T[8] = 2.0 * r;
+      break;
+    }
+    case 7: sym(0, 2); break;
+    case 8: T[0] = 0.5; T[4] = -0.5; break;
+    default: break;
+  }
+}
+
+DevOptics dev_optics(const wo_optics& o);
+
+// Direct-direct intensity I_bg = sum_q S(q) P(q)^2 on the grid (FP64), over
+// the rows and columns of the source disc's bounding box (one spare pixel).
+double host_ibg(const wo_optics& oo) {
+  const DevOptics d = dev_optics(oo);
+  const DetAxis da = det_axis(d);
+  double cy, cx;
+  source_centre(d, &cy, &cx);
+  const double dnu = fmin(1.0 / (oo.nx * oo.dx), 1.0 / (oo.ny * oo.dy));
+  const double hw = oo.edge_width * dnu;
+  const double rs = oo.na_ill / oo.wavelength + hw + dnu;
+  double bg = 0.0;
+  for (int ky = 0; ky < oo.ny; ++ky) {
+    const double fy = fftfreq(ky, oo.ny, oo.dy);
+    if (fabs(fy - cy) > rs) continue;
+    for (int kx = 0; kx < oo.nx; ++kx) {
+      const double fx = fftfreq(kx, oo.nx, oo.dx);
+      if (fabs(fx - cx) > rs) continue;
+      const double P = det_pupil(d, da, fy, fx, hw);
+      bg += disc(fy - cy, fx - cx, oo.na_ill / oo.wavelength, hw) * P * P;
+    }
+  }
+  return bg;
+}
+
+// Constants of one patch of the vector model (channels, property tensors,
+// normalisation); false if no direct light reaches the detector.
+bool vec_rec(const wo_optics& o, VecRec* r) {
+  memset(r, 0, sizeof(*r));
+  const cd I(0.0, 1.0);
+  cd J[5][2];
+  cd M[5][2][2];
+  int NS, C;
+  if (o.vec_channels == 0) {
+    NS = 1;
+    C = 4;
+    J[0][0] = cd(o.ill_jones[0], o.ill_jones[1]);
+    J[0][1] = cd(o.ill_jones[2], o.ill_jones[3]);
+    const cd sig[4][2][2] = {{{1.0, 0.0}, {0.0, 1.0}},
+                             {{1.0, 0.0}, {0.0, -1.0}},
+                             {{0.0, 1.0}, {1.0, 0.0}},
+                             {{0.0, -I}, {I, 0.0}}};
+    for (int c = 0; c < 4; ++c) {
+      r->state[c] = 0;
+      for (int i = 0; i < 2; ++i)
+        for (int k = 0; k < 2; ++k) M[c][i][k] = sig[c][i][k];
+    }
+  } else {
+    NS = 5;
+    C = 5;
+    pol5_states(o.swing, J);
+    const double r2 = 1.0 / sqrt(2.0);
+    const cd a[2] = {cd(r2, 0), cd(0, -r2)};   // the circular analyser (1, -i)/sqrt2
+    for (int c = 0; c < 5; ++c) {
+      r->state[c] = c;
+      for (int i = 0; i < 2; ++i)
+        for (int k = 0; k < 2; ++k) M[c][i][k] = a[i] * std::conj(a[k]);
+    }
+  }
+  for (int s = 0; s < NS; ++s)
+    for (int i = 0; i < 2; ++i) {
+      r->J[s][i][0] = (float)J[s][i].real();
+      r->J[s][i][1] = (float)J[s][i].imag();
+    }
+  for (int c = 0; c < C; ++c)
+    for (int ip = 0; ip < 2; ++ip) {
+      cd al = 0.0;
+      for (int i = 0; i < 2; ++i) al += std::conj(J[r->state[c]][i]) * M[c][i][ip];
+      r->alpha[c][ip][0] = (float)al.real();
+      r->alpha[c][ip][1] = (float)al.imag();
+    }
+  for (int p = 0; p < o.vec_nprops; ++p) {
+    double T[9];
+    sh_tensor(o.vec_props[p] / 2, T);
+    const bool im = o.vec_props[p] % 2 == 1;
+    for (int e = 0; e < 9; ++e) {
+      r->T[p][e][0] = im ? 0.f : (float)T[e];
+      r->T[p][e][1] = im ? (float)T[e] : 0.f;
+    }
+  }
+  const double ibg = host_ibg(o);
+  if (!(ibg > 0.0)) return false;
+  r->scale = (float)(1.0 / ((double)o.ny * o.nx * ibg));
+  r->C = C;
+  r->P = o.vec_nprops;
+  r->NS = NS;
+  return true;
+}
 
 Sampling sampling_of(const wo_optics* o) {
   Sampling s;
@@ -433,7 +585,17 @@ LatSupport tf_support(const wo_optics* o, int32_t n, const Shape& s, bool* compa
   return sup;
 }
 
+// Vector model: the optics, the per-patch constants, the field spectra
+// (6 + 3 per illumination state) and the real channel responses.
+size_t vec_ws(const wo_optics* o, int32_t n, const Shape& s) {
+  const int F = 6 + 3 * (o->vec_channels == 0 ? 1 : 5);
+  const size_t vox = (size_t)s.Z * s.Y * s.X;
+  return params_bytes(n) + align_up((size_t)n * sizeof(VecRec)) + align_up((size_t)n * F * vox * sizeof(float2)) +
+         align_up((size_t)n * s.C * s.P * vox * sizeof(float));
+}
+
 size_t tf_ws(const wo_optics* o, int32_t n, const Shape& s) {
+  if (o->model == WO_MODEL_VECTOR_3D) return vec_ws(o, n, s);
   const int nf = o->model == WO_MODEL_FLUOR_3D ? 1 : 2;
   const int nv = n * field_sets(o);
   size_t b = params_bytes(nv) + partials_bytes(o, nv);
@@ -1236,10 +1398,48 @@ int wo_lateral_support(const wo_optics* o, int32_t n, wo_support* out) {
   return WO_OK;
 }
 
+// The vector bank: field spectra, their inverse lateral transforms (Y by the
+// column passes, X by complex row passes), the per-voxel channel responses,
+// and the forward 3D transform of each response into tf [patch][C][P][Z][Y][Xh].
+static int run_vector_tf(const wo_optics* o, int32_t n, const Shape& s, float2* tf, void* ws, hipStream_t hs) {
+  const int NS = o->vec_channels == 0 ? 1 : 5;
+  const int F = 6 + 3 * NS;
+  std::vector<DevOptics> h(n);
+  std::vector<VecRec> vr(n);
+  for (int i = 0; i < n; ++i) {
+    h[i] = dev_optics(o[i]);
+    if (!vec_rec(o[i], &vr[i])) return WO_EINVAL;
+  }
+  const long vox = s.Z * s.Y * s.X;
+  char* w = (char*)ws;
+  DevOptics* dopt = (DevOptics*)w;
+  w += params_bytes(n);
+  VecRec* drec = (VecRec*)w;
+  w += align_up((size_t)n * sizeof(VecRec));
+  float2* fields = (float2*)w;
+  w += align_up((size_t)n * F * vox * sizeof(float2));
+  float* resp = (float*)w;
+  WO_TRY(launch_set_params(dopt, h.data(), n, hs));
+  WO_TRY(launch_set_vec(drec, vr.data(), n, hs));
+  const Sampling sm = sampling_of(o);
+  WO_TRY(launch_vec_spectra(dopt, drec, sm, n, NS, fields, hs));
+  WO_TRY(launch_cols(fields, (int)s.Y, s.X, (long)F * s.Z, (long)F * s.Z, n, 1.f, hs, "k_cols_vec"));
+  WO_TRY(launch_rows_c2c(fields, (int)s.X, (long)n * F * s.Z * s.Y, 1.f, hs));
+  WO_TRY(launch_vec_products(drec, fields, resp, vox, F, n, hs));
+  const long rows = (long)s.C * s.P * s.Z * s.Y;
+  const RowGroups g{rows, rows, rows, n};
+  WO_TRY(launch_rows_r2c(resp, tf, (int)s.X, g, hs));
+  const long planes = (long)s.C * s.P * s.Z;
+  WO_TRY(launch_cols(tf, (int)s.Y, s.Xh, planes, planes, n, -1.f, hs, "k_cols_y_tf"));
+  WO_TRY(launch_cols(tf, (int)s.Z, s.Y * s.Xh, (long)s.C * s.P, (long)s.C * s.P, n, -1.f, hs, "k_cols_z_tf"));
+  return WO_OK;
+}
+
 // Transfer-function synthesis of validated optics into tf_out (workspace
 // tf_ws bytes at ws).
 static int run_tf(const wo_optics* o, int32_t n, const Shape& s, void* tf_out, void* ws, hipStream_t hs,
                   bool band_out = false) {
+  if (o->model == WO_MODEL_VECTOR_3D) return run_vector_tf(o, n, s, (float2*)tf_out, ws, hs);
   const int fs = field_sets(o);
   const int nv = n * fs;          // field sets: patch i, aperture c at i * fs + c
   std::vector<DevOptics> h(nv);

@@ -167,8 +167,12 @@ __global__ __launch_bounds__(1024) void k_rows_c2r(const float2* __restrict__ in
   }
 }
 
+// 2048 elements per workgroup (256 threads of 8): measured on the row passes
+// of 1024- and 512-point rows against 1024 to 8192 elements and 2 to 8 per
+// thread, the C2R pass is 3-4 % faster than with 4096 and the R2C pass equal
+// within the run-to-run spread.
 static int lines_per_wg_for(int X) {
-  int L = 4096 / X;
+  int L = 2048 / X;
   if (L < 1) L = 1;
   if (L > 64) L = 64;
   while (L > 1 && (long)L * X > kMaxElems) --L;

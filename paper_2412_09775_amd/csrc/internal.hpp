@@ -245,4 +245,33 @@ hipError_t launch_adam(DevOptics* opt, TuneState* st, const Sampling& sm, int nv
 hipError_t launch_pick_best(const DevOptics* opt, const TuneState* st, int starts, int npatch,
                             DevOptics* ropt, float* eta, hipStream_t s);
 
+// ---------------------------------------------------------------- vector label-free bank
+
+// Constants of one patch of the vector model, computed on the host: the
+// Jones vector of each illumination state, each channel's analysed direct
+// state alpha_c = J_s^H M_c and its state s, the property tensors T_p
+// ([p][3 n + k]) and 1 / (Y X I_bg).
+struct VecRec {
+  float J[5][2][2];
+  float alpha[5][2][2];
+  int state[5];
+  float T[8][9][2];
+  float scale;
+  int C, P, NS;
+};
+hipError_t launch_set_vec(VecRec* dst, const VecRec* host, int n, hipStream_t s);
+// Field spectra fields [patch][f][z][y][x] on the full lateral grid: f < 6 the
+// detected scattered field of a unit dipole, u_i'n (f = 3 i' + n), then for
+// each illumination state s the direct arm S P E conj(e_k) (f = 6 + 3 s + k),
+// each times the propagator of plane z.
+hipError_t launch_vec_spectra(const DevOptics* opt, const VecRec* rec, const Sampling& sm, int npatch, int NS,
+                              float2* fields, hipStream_t s);
+// In-place unnormalised complex FFT of nrows contiguous rows of length X
+// (sign -1 forward, +1 inverse).
+hipError_t launch_rows_c2c(float2* data, int X, long nrows, float sign, hipStream_t s);
+// The real channel responses out [patch][C][P][vox] = 2 Re R_cp from the
+// transformed fields [patch][F][vox].
+hipError_t launch_vec_products(const VecRec* rec, const float2* fields, float* out, long vox, int F, int npatch,
+                               hipStream_t s);
+
 }  // namespace wo

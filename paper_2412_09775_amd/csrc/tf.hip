@@ -400,17 +400,24 @@ bool tf_fields_choice_ok(int Z, const FftChoice& c) {
   return c.w >= 1 && c.w <= Z && c.threads == 0 && c.plan == 0;
 }
 
-// About 480 workgroups: each evaluates the z-independent pupil factors of its
-// tile once (FP64 square roots and divisions) and reuses them for its planes.
-// Few planes per workgroup repeat that set-up, many leave too few waves to hide
-// the passes' waits: measured over 1..64 planes, 12 is best on 96x512x512 (60
-// tiles: 1 plane 117 us, 12 planes 53 us, 16 planes 65 us, 64 planes 148 us)
-// and on 64x1024x1024 (76 tiles: 1 plane 106 us, 12 planes 58 us, 64 planes
-// 154 us); the tuner picks the chunk by timing.
+// Each workgroup evaluates the z-independent pupil factors of its tile once
+// (FP64 square roots and divisions) and its first plane in full, then
+// advances the others by one complex multiply.  Few planes per workgroup
+// repeat that set-up, many leave too few waves to hide the passes' waits, and
+// a short last chunk of a half of the axis (the chunks do not cross its wrap)
+// costs nearly as much as a full one.  Measured over 4..16 planes, 12 is best
+// on 96x512x512 (60 tiles: 4 planes 80 us, 8 64 us, 12 55 us, 16 64 us) and on
+// 64x1024x1024 (76 tiles: 6 planes 67 us, 8 64 us, 10 74 us, 12 58 us, 16 65
+// us).  The default aims at about 480 workgroups and raises a chunk below 12
+// planes to 12 while that still leaves 256 workgroups; the tuner picks the
+// chunk by timing.
 FftChoice tf_fields_default(int Z, long tiles, long npatch) {
   Sampling sm{};
   sm.nz = Z;
-  return FftChoice{tf_z_chunk(sm, tiles, npatch, 480), 0, 0};
+  const int zc = tf_z_chunk(sm, tiles, npatch, 480);
+  if (zc < 12 && Z >= 12 && tiles * npatch * z_chunk_count(Z, (Z + 1) / 2, 12) >= 256)
+    return FftChoice{12, 0, 0};
+  return FftChoice{zc, 0, 0};
 }
 
 // Column-tile width of the field kernel: at most 4096 elements (512 threads)

@@ -1,0 +1,222 @@
+// Vector label-free transfer functions (Table 1, vector column, label-free row).
+//
+// The bank correlates two tensor-valued fields per plane z.  The detected
+// scattered field of a unit dipole along n, u_i'n = IFFT2[P_i'j G_jn prop],
+// and the detected direct field of the source times the conjugate incident
+// field that drives the dipole, v_ik = IFFT2[S P_ik' e_k' conj(e_k) prop].
+// The aplanatic pupil map Q(p) (3 x 2) gives both: the incident field of
+// source point q is e = Q J, the detection tensor is P E Q^T, and its
+// columns are transverse to the wave, so P E Q^T (I - k^ k^T) g = P E g Q^T.
+// The direct light reaches the detector as P E J, so v_ik = J_i w_k with
+// w_k = IFFT2[S P E conj(e_k) prop]: six u fields and three w fields per
+// illumination state.  A channel c (state s, analyser M_c) then responds to
+// property p (tensor T_p) with
+//   R_cp = 1 / (Y X I_bg) sum_n,k beta_n T_p^{nk} conj(w_k),
+//   beta_n = sum_i' alpha_c,i' u_i'n,  alpha_c = J_s^H M_c,
+// and H_cp = FFT3(2 Re R_cp).  The spectra are written on the full lateral
+// grid, inverse-transformed along Y (column passes) and X (row passes
+// below), multiplied per voxel, and the real responses transformed forward
+// by the row and column passes of the linear model.
+#include "internal.hpp"
+
+namespace wo {
+
+struct VecBatch {
+  VecRec r[4];
+};
+static_assert(sizeof(VecBatch) <= 3584, "kernel arguments are limited to 4 KiB");
+
+__global__ void k_set_vec(VecRec* dst, VecBatch b, int count) {
+  const int i = threadIdx.x;
+  if (i < count) dst[i] = b.r[i];
+}
+
+hipError_t launch_set_vec(VecRec* dst, const VecRec* host, int n, hipStream_t s) {
+  for (int i0 = 0; i0 < n; i0 += 4) {
+    VecBatch b;
+    const int cnt = n - i0 < 4 ? n - i0 : 4;
+    for (int j = 0; j < cnt; ++j) b.r[j] = host[i0 + j];
+    hipLaunchKernelGGL(k_set_vec, dim3(1), dim3(64), 0, s, dst + i0, b, cnt);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+// One thread per lateral frequency (ky, kx) of one patch: the pupil values
+// and the map Q in FP64, then every plane's propagator phase.  Q is written
+// without angles: with w = 1 / (k_m (k_m + kz)),
+//   Q = [[1 - px^2 w, -px py w], [-px py w, 1 - py^2 w], [-px / k_m, -py / k_m]].
+__global__ __launch_bounds__(256) void k_vec_spectra(const DevOptics* __restrict__ opt,
+                                                     const VecRec* __restrict__ rec, Sampling sm,
+                                                     float2* __restrict__ fields, int NS) {
+  const int kx = blockIdx.x * blockDim.x + threadIdx.x;
+  const int ky = blockIdx.y;
+  const long patch = blockIdx.z;
+  const int X = sm.nx, Y = sm.ny, Z = sm.nz;
+  if (kx >= X) return;
+  const DevOptics o = opt[patch];
+  const int F = 6 + 3 * NS;
+  const long plane = (long)Y * X;
+  float2* base = fields + patch * (long)F * Z * plane + (long)ky * X + kx;
+  const double fy = fftfreq(ky, Y, sm.dy), fx = fftfreq(kx, X, sm.dx);
+  const double hw = soft_halfwidth(o, sm);
+  const double km = o.n_medium / o.wavelength;
+  const DetAxis dax = det_axis(o);
+  const double P = det_pupil(o, dax, fy, fx, hw);
+  double cy, cx;
+  source_centre(o, &cy, &cx);
+  const double S = disc(fy - cy, fx - cx, o.na_ill / o.wavelength, hw);
+  const double kz = sqrt(fmax(km * km - (fy * fy + fx * fx), 0.0));
+  // u_i'n spectrum: i (P k_m / kz) Q_n,i' e^{i phi}; w_k: S P conj(e_k) e^{i phi}
+  float q[3][2] = {{0.f, 0.f}, {0.f, 0.f}, {0.f, 0.f}};
+  float gp = 0.f, sp = 0.f;
+  float2 ce[5][3];
+  if (P != 0.0 && kz > 0.0) {
+    const double w = 1.0 / (km * (km + kz));
+    q[0][0] = (float)(1.0 - fx * fx * w);
+    q[0][1] = (float)(-fx * fy * w);
+    q[1][0] = q[0][1];
+    q[1][1] = (float)(1.0 - fy * fy * w);
+    q[2][0] = (float)(-fx / km);
+    q[2][1] = (float)(-fy / km);
+    gp = (float)(P * km / kz);
+    sp = (float)(S * P);
+  }
+  for (int s = 0; s < NS; ++s) {
+    const float2 jx = make_float2(rec[patch].J[s][0][0], rec[patch].J[s][0][1]);
+    const float2 jy = make_float2(rec[patch].J[s][1][0], rec[patch].J[s][1][1]);
+#pragma unroll
+    for (int k = 0; k < 3; ++k)   // conj(e_k) = conj(Q_k0 Jx + Q_k1 Jy)
+      ce[s][k] = make_float2(q[k][0] * jx.x + q[k][1] * jy.x, -(q[k][0] * jx.y + q[k][1] * jy.y));
+  }
+  const double ab2 = (gp != 0.f) ? 2.0 * aberration_waves(o, fy, fx) : 0.0;
+  for (int z = 0; z < Z; ++z) {
+    float sn = 0.f, cs = 0.f;
+    if (gp != 0.f) {
+      const double arg = 2.0 * kz * (plane_z(z, sm) - o.defocus) + ab2;   // phase / pi
+      sincospif((float)(arg - 2.0 * rint(0.5 * arg)), &sn, &cs);
+    }
+    float2* pz = base + (long)z * plane;
+#pragma unroll
+    for (int ip = 0; ip < 2; ++ip)
+#pragma unroll
+      for (int n = 0; n < 3; ++n) {
+        const float a = gp * q[n][ip];
+        pz[(long)(3 * ip + n) * Z * plane] = make_float2(-a * sn, a * cs);   // i a e^{i phi}
+      }
+    for (int s = 0; s < NS; ++s)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const float2 c = ce[s][k];
+        const float2 e = make_float2(sp * cs, sp * sn);
+        pz[(long)(6 + 3 * s + k) * Z * plane] = make_float2(e.x * c.x - e.y * c.y, e.x * c.y + e.y * c.x);
+      }
+  }
+}
+
+hipError_t launch_vec_spectra(const DevOptics* opt, const VecRec* rec, const Sampling& sm, int npatch, int NS,
+                              float2* fields, hipStream_t s) {
+  if (NS < 1 || NS > 5 || npatch < 1 || npatch > 65535 || sm.ny > 65535) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)((sm.nx + 255) / 256), (unsigned)sm.ny, (unsigned)npatch);
+  ScopedTiming _t("k_vec_spectra", s);
+  hipLaunchKernelGGL(k_vec_spectra, grid, dim3(256), 0, s, opt, rec, sm, fields, NS);
+  return hipGetLastError();
+}
+
+// Complex FFT of L contiguous rows of length X per workgroup, in place and
+// unnormalised (sign -1 forward, +1 inverse), on the runtime plan.
+__global__ __launch_bounds__(1024) void k_rows_c2c(float2* __restrict__ data, int X, long nrows,
+                                                   FftPlan plan, int L, float sign) {
+  extern __shared__ float2 smem[];
+  float2* tw = smem;
+  float2* buf = smem + X;
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const long row0 = (long)blockIdx.x * L;
+  const int nl = (int)min((long)L, nrows - row0);
+  const int PS = pad_shift(X), LS = row_stride(X);
+  float2* rows = data + row0 * X;
+  auto slot = [&](int e) {
+    const int l = e / X;
+    return l * LS + row_slot(e - l * X, PS);
+  };
+  fill_twiddles(tw, X, tid, nthr);
+  gather2_to_lds(buf, nl * X, tid, nthr, [&](int e) { return rows[e]; }, [](int, float2 v) { return v; },
+                 slot, [] {});
+  __syncthreads();
+  fft_lines<0, 0, false, kEmax, true>(buf, LdsLines{nl, 1, LS, false, -1, true}, plan, tw, sign, tid,
+                                      nthr);
+  __syncthreads();
+  scatter_from_lds_map(buf, nl * X, tid, nthr, slot, [&](int e, float2 v) { rows[e] = v; });
+}
+
+hipError_t launch_rows_c2c(float2* data, int X, long nrows, float sign, hipStream_t s) {
+  if (X < 2 || nrows < 1) return hipErrorInvalidValue;
+  FftPlan plan;
+  if (!make_plan(X, &plan)) return hipErrorInvalidValue;
+  int L = 4096 / X;
+  if (L < 1) L = 1;
+  while (L > 1 && (long)L * X > kMaxElems) --L;
+  if ((long)L * X > kMaxElems) return hipErrorInvalidValue;
+  const size_t lds = (size_t)(X + (long)L * row_stride(X)) * sizeof(float2);
+  if ((long)lds > lds_limit_bytes()) return hipErrorInvalidValue;
+  const long nwg = (nrows + L - 1) / L;
+  const int thr = threads_for((long)L * X);
+  ScopedTiming _t("k_rows_c2c", s);
+  hipLaunchKernelGGL(k_rows_c2c, dim3((unsigned)nwg), dim3(thr), lds, s, data, X, nrows, plan, L, sign);
+  return hipGetLastError();
+}
+
+// One thread per voxel of one patch: beta_n = sum_i' alpha_c,i' u_i'n for
+// every channel, then 2 Re(sum_n,k T_p^{nk} beta_n conj(w_k)) / (Y X I_bg)
+// for every property.
+__global__ __launch_bounds__(256) void k_vec_products(const VecRec* __restrict__ rec,
+                                                      const float2* __restrict__ fields,
+                                                      float* __restrict__ out, long vox, int F) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long patch = blockIdx.y;
+  if (i >= vox) return;
+  const VecRec& r = rec[patch];
+  const int C = r.C, P = r.P, NS = r.NS;
+  const float2* fp = fields + patch * (long)F * vox + i;
+  float2 u[6], w[5][3];
+#pragma unroll
+  for (int f = 0; f < 6; ++f) u[f] = fp[(long)f * vox];
+  for (int s = 0; s < NS; ++s)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) w[s][k] = fp[(long)(6 + 3 * s + k) * vox];
+  const float sc = 2.f * r.scale;
+  float* op = out + patch * (long)C * P * vox + i;
+  for (int c = 0; c < C; ++c) {
+    const float2 a0 = make_float2(r.alpha[c][0][0], r.alpha[c][0][1]);
+    const float2 a1 = make_float2(r.alpha[c][1][0], r.alpha[c][1][1]);
+    const int s = r.state[c];
+    float2 qm[3][3];
+#pragma unroll
+    for (int n = 0; n < 3; ++n) {
+      const float2 b = cadd(cmul(a0, u[n]), cmul(a1, u[3 + n]));
+#pragma unroll
+      for (int k = 0; k < 3; ++k) qm[n][k] = cmul(b, make_float2(w[s][k].x, -w[s][k].y));
+    }
+    for (int p = 0; p < P; ++p) {
+      float acc = 0.f;
+#pragma unroll
+      for (int e = 0; e < 9; ++e) {
+        const float2 t = make_float2(r.T[p][e][0], r.T[p][e][1]);
+        acc += t.x * qm[e / 3][e % 3].x - t.y * qm[e / 3][e % 3].y;
+      }
+      op[(long)(c * P + p) * vox] = sc * acc;
+    }
+  }
+}
+
+hipError_t launch_vec_products(const VecRec* rec, const float2* fields, float* out, long vox, int F, int npatch,
+                               hipStream_t s) {
+  if (vox < 1 || npatch < 1 || npatch > 65535) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)((vox + 255) / 256), (unsigned)npatch);
+  ScopedTiming _t("k_vec_products", s);
+  hipLaunchKernelGGL(k_vec_products, grid, dim3(256), 0, s, rec, fields, out, vox, F);
+  return hipGetLastError();
+}
+
+}  // namespace wo

@@ -241,3 +241,34 @@ def test_nine_aperture_validity_is_the_oracles_lit_criterion(lib):
         assert (st == 0) == lit, (kw, st, lit)
         seen.add(lit)
     assert seen == {True, False}
+
+
+def test_vector_model_shape_and_validation_on_the_host(lib):
+    """The vector model's bank shape follows its channel set and property list;
+    malformed channel sets, property codes, Jones vectors and oblique detection
+    are rejected before any GPU work, as are mixed property lists in one call and
+    property counts the linear calls do not implement."""
+    v = dict(model=api.MODEL_VECTOR_3D, na_det=1.2)
+    assert api.bank_shape(_optics(**v))[:3] == (4, 4, 3)
+    assert api.bank_shape(_optics(vec_channels=1, vec_props=(0, 1), **v))[:3] == (5, 2, 3)
+    assert api.bank_shape(_optics(vec_props=tuple(range(8)), **v))[:3] == (4, 8, 3)
+    one = ctypes.c_void_p(1)
+
+    def tf_status(o):
+        return lib.wo_transfer_function(api.optics_array(o), 1 if not isinstance(o, list) else len(o), one, one,
+                                        1 << 40, None)
+
+    assert tf_status(_optics(vec_channels=2, **v)) == -1
+    assert tf_status(_optics(vec_props=(0, 18), **v)) == -1
+    assert tf_status(_optics(vec_props=(-1,), **v)) == -1
+    assert tf_status(_optics(vec_props=(), **v)) == -1
+    assert tf_status(_optics(ill_jones=(float("nan"), 1.0), **v)) == -1
+    assert tf_status(_optics(det_tilt=0.2, **dict(v, na_det=0.8))) == -2
+    assert tf_status([_optics(**v), _optics(vec_props=(0, 16, 8, 2), **v)]) == -1
+    with pytest.raises(ValueError):
+        api.optics_array(_optics(vec_props=tuple(range(9)), **v))
+    three = api.optics_array(_optics(vec_props=(0, 16, 8), **v))
+    assert lib.wo_reconstruct(three, 1, one, one, None, 1e-3, one, one, 1 << 40, None) == -2
+    assert lib.wo_forward(three, 1, one, one, None, one, one, 1 << 40, None) == -2
+    ws = api.workspace_size(_optics(**v), api.OP_TRANSFER_FUNCTION)
+    assert ws >= (9 * 8 + 16 * 4) * 32 * 64 * 64           # 9 fields + 16 responses of the synthesis

@@ -59,6 +59,12 @@ def sectors(nz=16, ny=64, nx=64, **kw):
     return o.replace(**kw)
 
 
+def vector(nz=12, ny=48, nx=40, **kw):
+    o = op.Optics(model=op.VECTOR_3D, nz=nz, ny=ny, nx=nx, dz=0.25, dy=0.1, dx=0.1,
+                  wavelength=0.532, na_ill=0.5, na_det=1.2, n_medium=1.33)
+    return o.replace(**kw)
+
+
 def thin(nz=32, ny=128, nx=128, **kw):
     o = op.Optics(model=op.LABELFREE_THIN, nz=nz, ny=ny, nx=nx, dz=0.2, dy=0.1, dx=0.1,
                   wavelength=0.532, na_ill=0.5, na_det=1.2, n_medium=1.33, edge_width=0.5)
@@ -127,6 +133,16 @@ CASES = {
     "fluor_oblique": [fluor(nz=24, ny=64, nx=64, na_det=0.8, det_tilt=0.4, det_azimuth=2.0, edge_width=0.5)],
     "pol5_oblique": [pol5(nz=12, ny=96, nx=96, det_tilt=0.3, det_azimuth=0.4, edge_width=0.5)],
     "thin_oblique": [thin(nz=16, ny=64, nx=64, na_det=0.9, det_tilt=0.3, det_azimuth=1.2)],
+    # vector (non-paraxial) label-free bank: Stokes channels under circular or
+    # elliptical illumination, the five swing states, 2 or 4 spherical-harmonic
+    # coefficients (phase, transverse birefringence, absorption; a z-coupled
+    # quadrupole); tilted, defocused, aberrated and soft-edged patches
+    "vector_stokes": [vector(tilt_zenith=0.2, tilt_azimuth=0.7, edge_width=0.5)],
+    "vector_stokes_p2_batch2": [vector(nz=8, ny=64, nx=64, vec_props=(0, 14), ill_jones=(1.0, 0.0)),
+                                vector(nz=8, ny=64, nx=64, vec_props=(0, 14), defocus=0.2,
+                                       ill_jones=(0.6, 0.8j), edge_width=0.5, zernike=(0.1, 0.0, 0.05))],
+    "vector_pol_states": [vector(nz=12, ny=64, nx=48, vec_channels=1, swing=0.08, defocus=-0.15,
+                                 edge_width=0.5)],
 }
 
 
@@ -145,6 +161,10 @@ def specimen(o, seed):
         return synth.fibres((o.nz, o.ny, o.nx), (o.dz, o.dy, o.dx), 6, seed)
     if o.model == op.SECTORS9_3D:
         return synth.ellipsoids((o.nz, o.ny, o.nx), (o.dz, o.dy, o.dx), 12, seed, semi_axes=(0.5, 1.5))[:1]
+    if o.model == op.VECTOR_3D:
+        if P == 4:
+            return synth.fibres((o.nz, o.ny, o.nx), (o.dz, o.dy, o.dx), 6, seed)
+        return synth.ellipsoids((o.nz, o.ny, o.nx), (o.dz, o.dy, o.dx), 12, seed, semi_axes=(0.5, 1.5))[:P]
     return synth.thin_cells((o.ny, o.nx), o.dx, 8, seed)
 
 

@@ -270,3 +270,15 @@ def test_spherical_harmonic_tensors_are_the_stated_basis():
     assert np.allclose(Y[4][:2, :2], tfm.pol5_property_matrices()[2])
     assert np.allclose(Y[6], np.diag([-1.0, -1.0, 2.0]) / (2 * math.sqrt(3.0)))
     assert np.allclose(vec.property_tensor(1), 1j * np.eye(3))
+
+
+def test_bank_at_one_frequency_is_the_bank():
+    """The direct source sum at one frequency equals the FFT-based bank there."""
+    o = vec_optics(nz=4, ny=8, nx=10, vec_props=(0, 16, 8, 1, 14, 7), tilt_zenith=0.15, defocus=0.1,
+                   zernike=(0.05, 0.0, -0.1), ill_jones=(0.6, 0.8j))
+    for chans in (vec.STOKES, vec.POL_STATES):
+        oc = o.replace(vec_channels=chans, swing=0.07)
+        bank = vec.vector_3d(oc)
+        for k in [(0, 0, 0), (1, 2, 3), (3, 7, 9), (2, 5, 1)]:
+            got = vec.vector_3d_at(oc, *k)
+            assert np.allclose(got, bank[(slice(None), slice(None)) + k], atol=1e-12 * np.abs(bank).max())
