@@ -48,6 +48,10 @@ LABELFREE = dict(_OPT, model=1, nz=96, ny=512, nx=512, dz=0.2, dy=0.1, dx=0.1, w
 # widefield fluorescence, 1 x 1
 FLUOR = dict(_OPT, model=0, nz=32, ny=64, nx=64, dz=0.25, dy=0.1, dx=0.1, wavelength=0.52, na_ill=0.0,
              na_det=1.2, n_medium=1.33)
+# vector (non-paraxial) label-free bank of the same 5 x 4 system as the headline:
+# the five swing states through the circular analyser, properties phase,
+# rho cos 2w, rho sin 2w, absorption (spherical-harmonic codes 0, 16, 8, 1)
+VECTOR = dict(POL5, model=5, vec_channels=1, vec_props=(0, 16, 8, 1))
 WORKLOAD = LABELFREE          # the 3D label-free sampling the extra sections reuse
 ETA_REL = 1e-3
 TOL_REC = 1e-4                # reconstruction parity (relative L2) vs the FP64 oracle
@@ -64,17 +68,22 @@ SECTIONS = {
     "fluor": dict(optics=FLUOR, name="fluor3d_32x64x64",
                   workload="widefield fluorescence, 32x64x64, 1 x 1, 50 beads + N(0, 1e-3^2) noise, "
                            "eta 1e-3 (full-layout calls)"),
+    "vector": dict(optics=VECTOR, name="vector_64x1024x1024",
+                   workload="vector (non-paraxial) label-free bank, 64x1024x1024, the 5 swing states x "
+                            "4 spherical-harmonic coefficients (phase, rho cos 2w, rho sin 2w, absorption), "
+                            "300 spline fibres + N(0, 1e-3^2) noise; full-layout calls, default schedules"),
 }
 
 
-def kernel_bytes(name, Z, Y, X, sup, C=1, P=2, E=None):
+def kernel_bytes(name, Z, Y, X, sup, C=1, P=2, E=None, F=None):
     """Algorithmic HBM bytes one launch of each kernel must move in the step.
 
     sup: the lateral support (wo_lateral_support): the fields A and B are kept on
     field_cols columns at ly points along y, the bank and the spectra on the
     columns k < kt of every row (of the band rows once transformed along Y).
     C, P: channels and properties; E: transfer-function values read per
-    frequency by the fused Z pass (C * P, or 2 for the reduced 5 x 4 bank)."""
+    frequency by the fused Z pass (C * P, or 2 for the reduced 5 x 4 bank); F: the
+    vector model's field count (its synthesis works on the full grid)."""
     E = C * P if E is None else E
     fa, fb = sup["field_cols"]
     kt, nb, (ly, _) = sup["tf_cols"], sup["band_rows"], sup["tf_lengths"]
@@ -100,6 +109,22 @@ def kernel_bytes(name, Z, Y, X, sup, C=1, P=2, E=None):
         # the same into the band layout (no zeros)
         "k_cols_z_band": 2 * 2 * cplx * band,
     }
+    if F is not None:
+        # vector synthesis: F field spectra written on the detection pupil's fb
+        # columns and transformed along Y there (read + write), then along X into
+        # full rows, read by the products, which write C P real responses; their
+        # forward transform on the bank's support (kt columns, band rows), whose
+        # Z pass writes the full half-spectrum bank
+        half_full = Z * Y * Xh
+        table.update({
+            "k_vec_spectra": F * cplx * Z * Y * fb,
+            "k_cols_vec": 2 * F * cplx * Z * Y * fb,
+            "k_rows_c2c": F * cplx * (Z * Y * fb + full),
+            "k_vec_products": F * cplx * full + C * P * 4 * full,
+            "k_rows_r2c_tf": C * P * (4 * full + cplx * rows_kt),
+            "k_cols_y_tf": C * P * cplx * (rows_kt + band),
+            "k_cols_expand": C * P * cplx * (band + half_full),
+        })
     return table.get(name)
 
 
@@ -294,12 +319,32 @@ def pol5_sigma_max_sq(api, torch, o, red):
     return best
 
 
+def bank_sigma_max_sq(torch, tf):
+    """max over frequencies of sigma_max(H(nu))^2 of a full bank tf (1, C, P, Z, Y, Xh):
+    per frequency the largest eigenvalue of H^H H by power iteration."""
+    C, P = tf.shape[1], tf.shape[2]
+    H = tf[0].reshape(C, P, -1)
+    best = 0.0
+    for s in range(0, H.shape[2], 1 << 21):
+        h = H[:, :, s:s + (1 << 21)]
+        G = [[sum(h[c, p].conj() * h[c, q] for c in range(C)) for q in range(P)] for p in range(P)]
+        x = [torch.ones_like(h[0, 0]) for _ in range(P)]
+        lam = None
+        for _ in range(60):
+            y = [sum(G[p][q] * x[q] for q in range(P)) for p in range(P)]
+            nrm = torch.sqrt(sum((t.abs() ** 2) for t in y)) + 1e-30
+            x = [t / nrm for t in y]
+            lam = nrm
+        best = max(best, float(lam.max()))
+    return best
+
+
 def make_inputs(api, torch, dev, key, o, sup):
     """The workload's synthetic data on the device (forward model of a seeded
     specimen through the GPU bank, plus noise) and eta.  Returns (d, eta, band)."""
     import synth
     Z, Y, X = o.nz, o.ny, o.nx
-    band = key != "fluor"
+    band = key not in ("fluor", "vector")
     tf = api.transfer_function_band([o], device=dev) if band else api.transfer_function([o], device=dev)
     lin = ((lambda op, x: api.linear_band(op, [o], tf, x)) if band else
            (lambda op, x: api.forward([o], tf, x)))
@@ -315,6 +360,12 @@ def make_inputs(api, torch, dev, key, o, sup):
         d = torch.from_numpy(synth.poisson_gaussian(clean.cpu().numpy(), seed=2002)).to(dev)
         # 1 channel: sigma_max^2 = |H_phase|^2 + |H_abs|^2
         eta = ETA_REL * float((tf.abs() ** 2).sum(dim=2).max())
+    elif key == "vector":
+        f = synth.fibres_on_device((Z, Y, X), (o.dz, o.dy, o.dx), 300, seed=3001, device=dev)[None]
+        d = api.forward([o], tf, f)
+        del f
+        api.add_gaussian_noise(d, 1e-3, 3002)
+        eta = ETA_REL * bank_sigma_max_sq(torch, tf)
     else:
         obj = synth.beads((Z, Y, X), 50, seed=1001)[None]
         clean = lin(api.OP_FORWARD, torch.from_numpy(obj[None]).to(dev))
@@ -330,7 +381,8 @@ def _oracle_optics(o):
     from oracle import optics as op
     return op.Optics(model=o.model, nz=o.nz, ny=o.ny, nx=o.nx, dz=o.dz, dy=o.dy, dx=o.dx,
                      wavelength=o.wavelength, na_ill=o.na_ill, na_det=o.na_det, n_medium=o.n_medium,
-                     swing=o.swing)
+                     swing=o.swing, vec_channels=o.vec_channels, vec_props=tuple(o.vec_props),
+                     ill_jones=tuple(o.ill_jones))
 
 
 def parity_full(o, d_host, f_gpu, eta):
@@ -372,12 +424,15 @@ def _dft_at(vol, freqs):
 def parity_pol5_sampled(o, d_host, f_gpu, eta, sup, n=12, seed=3003):
     """At sampled frequencies of the support: the oracle's per-frequency Tikhonov
     solve F = (H^H H + eta I)^-1 H^H D with H from the direct source sum
-    (oracle.tf.pol5_3d_at) and D the direct DFT of the bench's own data, against the
-    direct DFT of the timed GPU output there (relative L2 over the samples).  The
-    whole-volume FP64 solve does not fit the bench's time."""
+    (oracle.tf.pol5_3d_at, or oracle.vector.vector_3d_at for the vector bank) and D
+    the direct DFT of the bench's own data, against the direct DFT of the timed GPU
+    output there (relative L2 over the samples).  The whole-volume FP64 solve does
+    not fit the bench's time."""
     from oracle import tf as tfm
+    from oracle import vector as vec
     t0 = time.perf_counter()
     oo = _oracle_optics(o)
+    bank_at = vec.vector_3d_at if o.model == 5 else tfm.pol5_3d_at
     rng = np.random.default_rng(seed)
     ky_max = (sup["band_rows"] - 1) // 2
     kt = sup["tf_cols"]
@@ -393,14 +448,15 @@ def parity_pol5_sampled(o, d_host, f_gpu, eta, sup, n=12, seed=3003):
     Fg = _dft_at(f_gpu, freqs)                                           # (4, K)
     num = den = 0.0
     for k, (kz, ky, kx) in enumerate(freqs):
-        H = tfm.pol5_3d_at(oo, kz, ky, kx)
+        H = bank_at(oo, kz, ky, kx)
         Hh = H.conj().T
         F = np.linalg.solve(Hh @ H + eta * np.eye(4), Hh @ Dg[:, k])
         num += float(np.sum(np.abs(Fg[:, k] - F) ** 2))
         den += float(np.sum(np.abs(F) ** 2))
     err = math.sqrt(num / den)
     return {"kind": f"{n} sampled frequencies of the support",
-            "oracle": "oracle.tf.pol5_3d_at (direct source sum) + per-frequency solve; direct DFTs (FP64)",
+            "oracle": f"oracle.{'vector.vector_3d_at' if o.model == 5 else 'tf.pol5_3d_at'} (direct source "
+                      "sum) + per-frequency solve; direct DFTs (FP64)",
             "rel_l2": err, "tolerance": TOL_REC, "ok": bool(err < TOL_REC),
             "oracle_seconds": round(time.perf_counter() - t0, 1)}
 
@@ -463,7 +519,7 @@ def linear_section(api, torch, dev, args, key, parity=True):
     if args.fft_plans:
         api.fft_plans_import(open(args.fft_plans).read())
         tuner["imported"] = os.path.basename(args.fft_plans)
-    elif not args.no_fft_tune:
+    elif not args.no_fft_tune and key != "vector":
         before = api.fft_plans_export()
         tuner["ms_per_step_default_schedules"] = timed(full_step, args.steps)
         a = time.perf_counter()
@@ -514,6 +570,7 @@ def linear_section(api, torch, dev, args, key, parity=True):
     ms_rec = timed(step_rec, args.steps)      # cached transfer function
 
     E = 2 if key == "pol5" else None
+    F = 6 + 3 * (5 if o.vec_channels == 1 else 1) if key == "vector" else None
     # the fluorescence workload (about 10 MB) stays in the caches and its kernels
     # last a few microseconds each: launch- and latency-bound, no HBM roofline
     hbm = key != "fluor"
@@ -521,7 +578,7 @@ def linear_section(api, torch, dev, args, key, parity=True):
     step_bytes = 0
     for name, (cnt, tot) in sorted(kern.items()):
         per = tot / cnt
-        b = kernel_bytes(name, Z, Y, X, sup, C, P, E) if hbm else None
+        b = kernel_bytes(name, Z, Y, X, sup, C, P, E, F) if hbm else None
         ent = {"launches": cnt, "avg_ms": round(per, 5)}
         if b:
             ent["alg_bytes"] = b
@@ -531,7 +588,7 @@ def linear_section(api, torch, dev, args, key, parity=True):
         kernels[name] = ent
     dom_ms = dom_rec[1] / dom_rec[0]
     if hbm:
-        dom_b = kernel_bytes(dom, Z, Y, X, sup, C, P, E) or 0
+        dom_b = kernel_bytes(dom, Z, Y, X, sup, C, P, E, F) or 0
         ach = dom_b / (dom_ms * 1e-3) / 1e9
         symbols = counter_symbols(sup, Z, X, P, C)
         roof = {"kernel": dom, "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
@@ -558,7 +615,7 @@ def linear_section(api, torch, dev, args, key, parity=True):
           f"{dom_ms * 1e3:.1f} us" + (f", {ach:.0f} GB/s" if hbm else ""), file=sys.stderr, flush=True)
     if parity:
         d_host = d.cpu().numpy()[0]
-        res["parity"] = (parity_pol5_sampled(o, d_host, f_timed, eta, sup) if key == "pol5"
+        res["parity"] = (parity_pol5_sampled(o, d_host, f_timed, eta, sup) if key in ("pol5", "vector")
                          else parity_full(o, d_host, f_timed, eta))
         print(f"[bench] {key}: parity {res['parity']['rel_l2']:.2e} ({res['parity']['kind']})",
               file=sys.stderr, flush=True)
@@ -584,7 +641,7 @@ def main():
     ap.add_argument("--fov-size", type=int, default=2048, help="field of view side (0: skip)")
     ap.add_argument("--no-multi-aperture", action="store_true")
     ap.add_argument("--no-aberration", action="store_true")
-    ap.add_argument("--sections", default="pol5,labelfree,fluor",
+    ap.add_argument("--sections", default="pol5,labelfree,fluor,vector",
                     help="linear workloads to run, the first is the headline")
     ap.add_argument("--main-only", action="store_true",
                     help="only the headline linear workload (profiled runs: only its kernels in the trace)")

@@ -226,21 +226,27 @@ def vector_3d_at(o: op.Optics, kz: int, ky: int, kx: int) -> np.ndarray:
     kzz = op.axial_wavenumber(o)
     zs = op.z_planes_3d(o) - o.defocus
 
-    def lateral(c, J, M, T, ny_, nx_):
-        e = incident_field(o, J)
-        Pe = np.einsum("yxij,yxj->yxi", Pt, e)
+    Q = pupil_map(o)[qy, qx]                                                             # (q, 3, 2)
+    # scattered arm at q + nu and q - nu, and the z phases of the two correlations
+    arms = []
+    for ny_, nx_ in ((ky, kx), ((-ky) % o.ny, (-kx) % o.nx)):
         py, px = (qy + ny_) % o.ny, (qx + nx_) % o.nx
-        V = S[qy, qx, None, None] * Pe[qy, qx, :, None] * np.conj(e[qy, qx, None, :])   # (q, i, k)
-        U = PG[py, px]                                                                   # (q, i', n)
-        w = np.einsum("ab,qak,qbn,nk->q", M, np.conj(V), U, T)
         dk = kzz[py, px] - kzz[qy, qx]
-        return np.exp(2j * np.pi * np.outer(zs, dk)) @ w / ibg                          # (Z,)
+        arms.append((PG[py, px], np.exp(2j * np.pi * np.outer(zs, dk)) / ibg))          # (q, i', n), (Z, q)
+
+    def lateral(V, M, T, arm):
+        U, ph = arm
+        w = np.einsum("ab,qak,qbn,nk->q", M, np.conj(V), U, T, optimize=True)
+        return ph @ w                                                                    # (Z,)
 
     ez = np.exp(-2j * np.pi * kz * np.arange(o.nz) / o.nz)
     out = np.empty((len(chans), len(props)), dtype=np.complex128)
     for c, (J, M) in enumerate(chans):
+        e = Q @ np.asarray(J, dtype=np.complex128)                                       # e(q) = Q J
+        Pe = np.einsum("qij,qj->qi", Pt[qy, qx], e)
+        V = S[qy, qx, None, None] * Pe[:, :, None] * np.conj(e[:, None, :])              # (q, i, k)
         for p, T in enumerate(props):
-            cp = lateral(c, J, M, T, ky, kx)
-            cm = lateral(c, J, M, T, (-ky) % o.ny, (-kx) % o.nx)
+            cp = lateral(V, M, T, arms[0])
+            cm = lateral(V, M, T, arms[1])
             out[c, p] = np.sum(ez * (cp + np.conj(cm)))
     return out

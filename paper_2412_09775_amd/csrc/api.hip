@@ -585,12 +585,21 @@ LatSupport tf_support(const wo_optics* o, int32_t n, const Shape& s, bool* compa
   return sup;
 }
 
-// Vector model: the optics, the per-patch constants, the field spectra
-// (6 + 3 per illumination state) and the real channel responses.
+// Vector model: the optics, the per-patch constants, the field spectra on the
+// detection pupil's columns (later the bank's columns k < kt before its Z
+// pass), the fields on the grid (6 + 3 per illumination state each) and the
+// real channel responses.
+size_t vec_compact_elems(const wo_optics* o, int32_t n, const Shape& s, const LatSupport& sup) {
+  const long F = 6 + 3 * (o->vec_channels == 0 ? 1 : 5);
+  return (size_t)n * s.Z * s.Y * std::max(F * sup.xc, (long)s.C * s.P * sup.kt);
+}
+
 size_t vec_ws(const wo_optics* o, int32_t n, const Shape& s) {
   const int F = 6 + 3 * (o->vec_channels == 0 ? 1 : 5);
   const size_t vox = (size_t)s.Z * s.Y * s.X;
-  return params_bytes(n) + align_up((size_t)n * sizeof(VecRec)) + align_up((size_t)n * F * vox * sizeof(float2)) +
+  const LatSupport sup = lateral_support(o, n);
+  return params_bytes(n) + align_up((size_t)n * sizeof(VecRec)) +
+         align_up(vec_compact_elems(o, n, s, sup) * sizeof(float2)) + align_up((size_t)n * F * vox * sizeof(float2)) +
          align_up((size_t)n * s.C * s.P * vox * sizeof(float));
 }
 
@@ -1411,27 +1420,34 @@ static int run_vector_tf(const wo_optics* o, int32_t n, const Shape& s, float2* 
     if (!vec_rec(o[i], &vr[i])) return WO_EINVAL;
   }
   const long vox = s.Z * s.Y * s.X;
+  const LatSupport sup = lateral_support(o, n);   // the detection pupils' columns: sup.xc, sup.kp
   char* w = (char*)ws;
   DevOptics* dopt = (DevOptics*)w;
   w += params_bytes(n);
   VecRec* drec = (VecRec*)w;
   w += align_up((size_t)n * sizeof(VecRec));
+  float2* spec = (float2*)w;
+  w += align_up(vec_compact_elems(o, n, s, sup) * sizeof(float2));
   float2* fields = (float2*)w;
   w += align_up((size_t)n * F * vox * sizeof(float2));
   float* resp = (float*)w;
   WO_TRY(launch_set_params(dopt, h.data(), n, hs));
   WO_TRY(launch_set_vec(drec, vr.data(), n, hs));
   const Sampling sm = sampling_of(o);
-  WO_TRY(launch_vec_spectra(dopt, drec, sm, n, NS, fields, hs));
-  WO_TRY(launch_cols(fields, (int)s.Y, s.X, (long)F * s.Z, (long)F * s.Z, n, 1.f, hs, "k_cols_vec"));
-  WO_TRY(launch_rows_c2c(fields, (int)s.X, (long)n * F * s.Z * s.Y, 1.f, hs));
+  WO_TRY(launch_vec_spectra(dopt, drec, sm, n, NS, spec, sup.xc, sup.kp, hs));
+  WO_TRY(launch_cols(spec, (int)s.Y, sup.xc, (long)F * s.Z, (long)F * s.Z, n, 1.f, hs, "k_cols_vec"));
+  WO_TRY(launch_rows_c2c(spec, fields, (int)s.X, sup.xc, sup.kp, (long)n * F * s.Z * s.Y, 1.f, hs));
   WO_TRY(launch_vec_products(drec, fields, resp, vox, F, n, hs));
+  // the bank vanishes outside the columns k < kt and the band rows: the X and
+  // Y transforms keep those (in the spectra's buffer), the Z pass writes the
+  // full bank with zeros elsewhere
   const long rows = (long)s.C * s.P * s.Z * s.Y;
   const RowGroups g{rows, rows, rows, n};
-  WO_TRY(launch_rows_r2c(resp, tf, (int)s.X, g, hs));
+  WO_TRY(launch_rows_r2c(resp, spec, (int)s.X, g, hs, sup.kt, sup.kt, "k_rows_r2c_tf"));
   const long planes = (long)s.C * s.P * s.Z;
-  WO_TRY(launch_cols(tf, (int)s.Y, s.Xh, planes, planes, n, -1.f, hs, "k_cols_y_tf"));
-  WO_TRY(launch_cols(tf, (int)s.Z, s.Y * s.Xh, (long)s.C * s.P, (long)s.C * s.P, n, -1.f, hs, "k_cols_z_tf"));
+  WO_TRY(launch_cols(spec, (int)s.Y, sup.kt, planes, planes, n, -1.f, hs, "k_cols_y_tf", 1, sup.ky));
+  WO_TRY(launch_cols_expand(spec, tf, (int)s.Z, (int)s.Y, (int)s.Y, (int)s.Xh, sup.kt, sup.ky,
+                            (long)n * s.C * s.P, -1.f, hs));
   return WO_OK;
 }
 

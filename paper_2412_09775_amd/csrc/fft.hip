@@ -218,13 +218,13 @@ static FftChoice rows_choice(const FftKey& k) {
     return hipGetLastError();
 
 hipError_t launch_rows_r2c(const float* in, float2* out, int X, const RowGroups& g, hipStream_t s,
-                           int kt, int pitch) {
+                           int kt, int pitch, const char* tag) {
   const int Xh = X / 2 + 1;
   const int KT = kt > 0 ? kt : Xh, OP = pitch > 0 ? pitch : Xh;
   if (KT > Xh || OP < KT) return hipErrorInvalidValue;
   const long nrows = g.rows_per_group * g.ngroups;
   const FftKey key{kFftRowsR2C, X, 0, nrows, 0};
-  if (fft_recording()) fft_record(key, [=] { return launch_rows_r2c(in, out, X, g, s, KT, OP); });
+  if (fft_recording()) fft_record(key, [=] { return launch_rows_r2c(in, out, X, g, s, KT, OP, tag); });
   const FftChoice c = rows_choice(key);
   FftPlan plan;
   if (!make_plan_variant(X, c.plan, &plan)) return hipErrorInvalidValue;
@@ -233,7 +233,7 @@ hipError_t launch_rows_r2c(const float* in, float2* out, int X, const RowGroups&
   const long nwg = (nlines + L - 1) / L;
   const int thr = c.threads;
   const size_t lds = (size_t)(X + (long)L * row_stride(X)) * sizeof(float2);
-  ScopedTiming _t("k_rows_r2c", s);
+  ScopedTiming _t(tag, s);
 #define WO_ROWS_ARGS in, out, X, g, plan, L, nlines, KT, OP
 #define X_(NN) WO_CASE_ROWS(k_rows_r2c, NN)
   if (c.plan == 0) switch (X) {

@@ -109,7 +109,7 @@ struct RowGroups {
 // Real rows -> half-spectrum rows (forward, unnormalised): the columns k < kt
 // (0: all X/2 + 1) of each output row, row pitch `pitch` (0: X/2 + 1).
 hipError_t launch_rows_r2c(const float* in, float2* out, int X, const RowGroups& g, hipStream_t s,
-                           int kt = 0, int pitch = 0);
+                           int kt = 0, int pitch = 0, const char* tag = "k_rows_r2c");
 // Half-spectrum rows -> real rows times `scale` (inverse); input rows of
 // pitch `pitch` hold the columns k < kt, the others are taken as zero.
 hipError_t launch_rows_c2r(const float2* in, float* out, int X, const RowGroups& g, float scale,
@@ -260,15 +260,16 @@ struct VecRec {
   int C, P, NS;
 };
 hipError_t launch_set_vec(VecRec* dst, const VecRec* host, int n, hipStream_t s);
-// Field spectra fields [patch][f][z][y][x] on the full lateral grid: f < 6 the
-// detected scattered field of a unit dipole, u_i'n (f = 3 i' + n), then for
-// each illumination state s the direct arm S P E conj(e_k) (f = 6 + 3 s + k),
-// each times the propagator of plane z.
+// Field spectra fields [patch][f][z][y][c] on the XC kept columns c (column kx
+// = field_column(c, KP, X, XC)): f < 6 the detected scattered field of a unit
+// dipole, u_i'n (f = 3 i' + n), then for each illumination state s the direct
+// arm S P E conj(e_k) (f = 6 + 3 s + k), each times the propagator of plane z.
 hipError_t launch_vec_spectra(const DevOptics* opt, const VecRec* rec, const Sampling& sm, int npatch, int NS,
-                              float2* fields, hipStream_t s);
-// In-place unnormalised complex FFT of nrows contiguous rows of length X
-// (sign -1 forward, +1 inverse).
-hipError_t launch_rows_c2c(float2* data, int X, long nrows, float sign, hipStream_t s);
+                              float2* fields, int XC, int KP, hipStream_t s);
+// Unnormalised complex FFT along X (sign -1 forward, +1 inverse) of nrows rows:
+// src rows hold the XC kept columns (the others zero), dst rows all X values.
+hipError_t launch_rows_c2c(const float2* src, float2* dst, int X, int XC, int KP, long nrows, float sign,
+                           hipStream_t s);
 // The real channel responses out [patch][C][P][vox] = 2 Re R_cp from the
 // transformed fields [patch][F][vox].
 hipError_t launch_vec_products(const VecRec* rec, const float2* fields, float* out, long vox, int F, int npatch,

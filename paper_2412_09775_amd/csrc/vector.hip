@@ -13,10 +13,12 @@
 // property p (tensor T_p) with
 //   R_cp = 1 / (Y X I_bg) sum_n,k beta_n T_p^{nk} conj(w_k),
 //   beta_n = sum_i' alpha_c,i' u_i'n,  alpha_c = J_s^H M_c,
-// and H_cp = FFT3(2 Re R_cp).  The spectra are written on the full lateral
-// grid, inverse-transformed along Y (column passes) and X (row passes
-// below), multiplied per voxel, and the real responses transformed forward
-// by the row and column passes of the linear model.
+// and H_cp = FFT3(2 Re R_cp).  The spectra vanish outside the detection
+// pupil's columns: they are written on those columns only, inverse-
+// transformed along Y there (column passes), then along X into full rows
+// (row passes below, zeros for the other columns), multiplied per voxel, and
+// the real responses transformed forward by the row and column passes of the
+// linear model.
 #include "internal.hpp"
 
 namespace wo {
@@ -49,16 +51,17 @@ hipError_t launch_set_vec(VecRec* dst, const VecRec* host, int n, hipStream_t s)
 //   Q = [[1 - px^2 w, -px py w], [-px py w, 1 - py^2 w], [-px / k_m, -py / k_m]].
 __global__ __launch_bounds__(256) void k_vec_spectra(const DevOptics* __restrict__ opt,
                                                      const VecRec* __restrict__ rec, Sampling sm,
-                                                     float2* __restrict__ fields, int NS) {
-  const int kx = blockIdx.x * blockDim.x + threadIdx.x;
+                                                     float2* __restrict__ fields, int NS, int XC, int KP) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
   const int ky = blockIdx.y;
   const long patch = blockIdx.z;
   const int X = sm.nx, Y = sm.ny, Z = sm.nz;
-  if (kx >= X) return;
+  if (c >= XC) return;
+  const int kx = field_column(c, KP, X, XC);
   const DevOptics o = opt[patch];
   const int F = 6 + 3 * NS;
-  const long plane = (long)Y * X;
-  float2* base = fields + patch * (long)F * Z * plane + (long)ky * X + kx;
+  const long plane = (long)Y * XC;
+  float2* base = fields + patch * (long)F * Z * plane + (long)ky * XC + c;
   const double fy = fftfreq(ky, Y, sm.dy), fx = fftfreq(kx, X, sm.dx);
   const double hw = soft_halfwidth(o, sm);
   const double km = o.n_medium / o.wavelength;
@@ -116,45 +119,72 @@ __global__ __launch_bounds__(256) void k_vec_spectra(const DevOptics* __restrict
 }
 
 hipError_t launch_vec_spectra(const DevOptics* opt, const VecRec* rec, const Sampling& sm, int npatch, int NS,
-                              float2* fields, hipStream_t s) {
+                              float2* fields, int XC, int KP, hipStream_t s) {
   if (NS < 1 || NS > 5 || npatch < 1 || npatch > 65535 || sm.ny > 65535) return hipErrorInvalidValue;
-  const dim3 grid((unsigned)((sm.nx + 255) / 256), (unsigned)sm.ny, (unsigned)npatch);
+  if (XC < 1 || XC > sm.nx || KP < 0 || KP >= XC) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)((XC + 255) / 256), (unsigned)sm.ny, (unsigned)npatch);
   ScopedTiming _t("k_vec_spectra", s);
-  hipLaunchKernelGGL(k_vec_spectra, grid, dim3(256), 0, s, opt, rec, sm, fields, NS);
+  hipLaunchKernelGGL(k_vec_spectra, grid, dim3(256), 0, s, opt, rec, sm, fields, NS, XC, KP);
   return hipGetLastError();
 }
 
-// Complex FFT of L contiguous rows of length X per workgroup, in place and
-// unnormalised (sign -1 forward, +1 inverse), on the runtime plan.
-__global__ __launch_bounds__(1024) void k_rows_c2c(float2* __restrict__ data, int X, long nrows,
-                                                   FftPlan plan, int L, float sign) {
+// Complex FFT along X of L rows per workgroup (unnormalised; sign -1 forward,
+// +1 inverse): row r of src holds the XC kept columns of the spectrum
+// (field_column order, the others zero), row r of dst receives all X values.
+// Compiled lengths (NS > 0) take the first pass from memory and write the
+// last one to memory from registers, as the real row passes do; other
+// lengths use the runtime plan.
+template <int NS>
+__global__ __launch_bounds__(1024) void k_rows_c2c(const float2* __restrict__ src, float2* __restrict__ dst,
+                                                   int X, int XC, int KP, long nrows, FftPlan plan, int L,
+                                                   float sign) {
   extern __shared__ float2 smem[];
   float2* tw = smem;
   float2* buf = smem + X;
   const int tid = threadIdx.x, nthr = blockDim.x;
   const long row0 = (long)blockIdx.x * L;
   const int nl = (int)min((long)L, nrows - row0);
-  const int PS = pad_shift(X), LS = row_stride(X);
-  float2* rows = data + row0 * X;
-  auto slot = [&](int e) {
-    const int l = e / X;
-    return l * LS + row_slot(e - l * X, PS);
+  const int Xc = NS > 0 ? NS : X;
+  const int PS = pad_shift(Xc), LS = row_stride(Xc);
+  const float2* in = src + row0 * XC;
+  float2* out = dst + row0 * Xc;
+  // the condition depends on the index only, so the loads stay in flight together
+  auto load = [&](int l, int k) {
+    const int c = compact_column(k, KP, Xc, XC);
+    return c >= 0 ? in[(long)l * XC + c] : make_float2(0.f, 0.f);
   };
-  fill_twiddles(tw, X, tid, nthr);
-  gather2_to_lds(buf, nl * X, tid, nthr, [&](int e) { return rows[e]; }, [](int, float2 v) { return v; },
-                 slot, [] {});
-  __syncthreads();
-  fft_lines<0, 0, false, kEmax, true>(buf, LdsLines{nl, 1, LS, false, -1, true}, plan, tw, sign, tid,
-                                      nthr);
-  __syncthreads();
-  scatter_from_lds_map(buf, nl * X, tid, nthr, slot, [&](int e, float2 v) { rows[e] = v; });
+  fill_twiddles(tw, Xc, tid, nthr);
+  if constexpr (NS > 0) {
+    constexpr int NP = StaticPlan<NS>::passes();
+    auto finish = [](int, int, float2 v) { return v; };
+    auto store = [&](int l, int i, float2 v) { out[(long)l * NS + i] = v; };
+    first_pass_in2<NS, 0, false, kEmax, true, false>(buf, nl, 1, LS, -1, sign, tid, nthr, load, finish,
+                                                     [] {});
+    static_passes<NS, 0, false, kEmax, true, false, 1, NP - 1>(buf, nl, 1, LS, -1, tw, sign, tid, nthr);
+    last_pass_out<NS, 0, false, kEmax, true, false>(buf, nl, 1, LS, -1, tw, sign, tid, nthr, store);
+  } else {
+    auto slot = [&](int e) {
+      const int l = e / Xc;
+      return l * LS + row_slot(e - l * Xc, PS);
+    };
+    gather2_to_lds(buf, nl * Xc, tid, nthr, [&](int e) {
+      const int l = e / Xc;
+      return load(l, e - l * Xc);
+    }, [](int, float2 v) { return v; }, slot, [] {});
+    __syncthreads();
+    fft_lines<0, 0, false, kEmax, true>(buf, LdsLines{nl, 1, LS, false, -1, true}, plan, tw, sign, tid,
+                                        nthr);
+    __syncthreads();
+    scatter_from_lds_map(buf, nl * Xc, tid, nthr, slot, [&](int e, float2 v) { out[e] = v; });
+  }
 }
 
-hipError_t launch_rows_c2c(float2* data, int X, long nrows, float sign, hipStream_t s) {
-  if (X < 2 || nrows < 1) return hipErrorInvalidValue;
+hipError_t launch_rows_c2c(const float2* src, float2* dst, int X, int XC, int KP, long nrows, float sign,
+                           hipStream_t s) {
+  if (X < 2 || nrows < 1 || XC < 1 || XC > X || KP < 0 || KP >= XC) return hipErrorInvalidValue;
   FftPlan plan;
   if (!make_plan(X, &plan)) return hipErrorInvalidValue;
-  int L = 4096 / X;
+  int L = 2048 / X;   // 2048 elements per workgroup, as the real row passes
   if (L < 1) L = 1;
   while (L > 1 && (long)L * X > kMaxElems) --L;
   if ((long)L * X > kMaxElems) return hipErrorInvalidValue;
@@ -163,7 +193,19 @@ hipError_t launch_rows_c2c(float2* data, int X, long nrows, float sign, hipStrea
   const long nwg = (nrows + L - 1) / L;
   const int thr = threads_for((long)L * X);
   ScopedTiming _t("k_rows_c2c", s);
-  hipLaunchKernelGGL(k_rows_c2c, dim3((unsigned)nwg), dim3(thr), lds, s, data, X, nrows, plan, L, sign);
+#define X_(NN)                                                                                       \
+  case NN:                                                                                           \
+    hipLaunchKernelGGL((k_rows_c2c<NN>), dim3((unsigned)nwg), dim3(thr), lds, s, src, dst, X, XC, KP, \
+                       nrows, plan, L, sign);                                                        \
+    return hipGetLastError();
+  switch (X) {
+    WO_LATERAL_SIZES(X_)
+    default:
+      break;
+  }
+#undef X_
+  hipLaunchKernelGGL((k_rows_c2c<0>), dim3((unsigned)nwg), dim3(thr), lds, s, src, dst, X, XC, KP, nrows, plan,
+                     L, sign);
   return hipGetLastError();
 }
 
