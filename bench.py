@@ -71,7 +71,8 @@ SECTIONS = {
     "vector": dict(optics=VECTOR, name="vector_64x1024x1024",
                    workload="vector (non-paraxial) label-free bank, 64x1024x1024, the 5 swing states x "
                             "4 spherical-harmonic coefficients (phase, rho cos 2w, rho sin 2w, absorption), "
-                            "300 spline fibres + N(0, 1e-3^2) noise; full-layout calls, default schedules"),
+                            "300 spline fibres + N(0, 1e-3^2) noise; bank in the band layout, default "
+                            "schedules"),
 }
 
 
@@ -124,6 +125,7 @@ def kernel_bytes(name, Z, Y, X, sup, C=1, P=2, E=None, F=None):
             "k_rows_r2c_tf": C * P * (4 * full + cplx * rows_kt),
             "k_cols_y_tf": C * P * cplx * (rows_kt + band),
             "k_cols_expand": C * P * cplx * (band + half_full),
+            "k_cols_z_band": 2 * C * P * cplx * band,
         })
     return table.get(name)
 
@@ -344,7 +346,7 @@ def make_inputs(api, torch, dev, key, o, sup):
     specimen through the GPU bank, plus noise) and eta.  Returns (d, eta, band)."""
     import synth
     Z, Y, X = o.nz, o.ny, o.nx
-    band = key not in ("fluor", "vector")
+    band = key != "fluor"
     tf = api.transfer_function_band([o], device=dev) if band else api.transfer_function([o], device=dev)
     lin = ((lambda op, x: api.linear_band(op, [o], tf, x)) if band else
            (lambda op, x: api.forward([o], tf, x)))
@@ -362,7 +364,7 @@ def make_inputs(api, torch, dev, key, o, sup):
         eta = ETA_REL * float((tf.abs() ** 2).sum(dim=2).max())
     elif key == "vector":
         f = synth.fibres_on_device((Z, Y, X), (o.dz, o.dy, o.dx), 300, seed=3001, device=dev)[None]
-        d = api.forward([o], tf, f)
+        d = lin(api.OP_FORWARD, f)
         del f
         api.add_gaussian_noise(d, 1e-3, 3002)
         eta = ETA_REL * bank_sigma_max_sq(torch, tf)

@@ -227,9 +227,9 @@ int wo_reconstruct(const wo_optics* o, int32_t n, const void* tf, const float* d
  * k < tf_cols of the half spectrum; every other value of the full bank is zero
  * and implied, as the Hermitian half is.  The values are those
  * wo_transfer_function writes there, bit for bit.  Label-free 3D models
- * (one or nine apertures), the polarisation model, or any 3D model whose
- * support fills the grid (then the layout is the full one); others:
- * WO_EUNSUPPORTED.  Workspace as for wo_transfer_function.
+ * (one or nine apertures), the polarisation model, the vector model, or any
+ * 3D model whose support fills the grid (then the layout is the full one);
+ * others: WO_EUNSUPPORTED.  Workspace as for wo_transfer_function.
  *
  * POL5_3D is stored in reduced form: its 5 x 4 bank is a constant mix of the
  * label-free pair, H_cp = Re(kappa_cp) H_phase + Im(kappa_cp) H_abs (the

@@ -1410,7 +1410,8 @@ int wo_lateral_support(const wo_optics* o, int32_t n, wo_support* out) {
 // The vector bank: field spectra, their inverse lateral transforms (Y by the
 // column passes, X by complex row passes), the per-voxel channel responses,
 // and the forward 3D transform of each response into tf [patch][C][P][Z][Y][Xh].
-static int run_vector_tf(const wo_optics* o, int32_t n, const Shape& s, float2* tf, void* ws, hipStream_t hs) {
+static int run_vector_tf(const wo_optics* o, int32_t n, const Shape& s, float2* tf, void* ws, hipStream_t hs,
+                         bool band_out) {
   const int NS = o->vec_channels == 0 ? 1 : 5;
   const int F = 6 + 3 * NS;
   std::vector<DevOptics> h(n);
@@ -1440,14 +1441,14 @@ static int run_vector_tf(const wo_optics* o, int32_t n, const Shape& s, float2* 
   WO_TRY(launch_vec_products(drec, fields, resp, vox, F, n, hs));
   // the bank vanishes outside the columns k < kt and the band rows: the X and
   // Y transforms keep those (in the spectra's buffer), the Z pass writes the
-  // full bank with zeros elsewhere
+  // full bank with zeros elsewhere, or the band layout (band_out)
   const long rows = (long)s.C * s.P * s.Z * s.Y;
   const RowGroups g{rows, rows, rows, n};
   WO_TRY(launch_rows_r2c(resp, spec, (int)s.X, g, hs, sup.kt, sup.kt, "k_rows_r2c_tf"));
   const long planes = (long)s.C * s.P * s.Z;
   WO_TRY(launch_cols(spec, (int)s.Y, sup.kt, planes, planes, n, -1.f, hs, "k_cols_y_tf", 1, sup.ky));
   WO_TRY(launch_cols_expand(spec, tf, (int)s.Z, (int)s.Y, (int)s.Y, (int)s.Xh, sup.kt, sup.ky,
-                            (long)n * s.C * s.P, -1.f, hs));
+                            (long)n * s.C * s.P, -1.f, hs, band_out));
   return WO_OK;
 }
 
@@ -1455,7 +1456,7 @@ static int run_vector_tf(const wo_optics* o, int32_t n, const Shape& s, float2* 
 // tf_ws bytes at ws).
 static int run_tf(const wo_optics* o, int32_t n, const Shape& s, void* tf_out, void* ws, hipStream_t hs,
                   bool band_out = false) {
-  if (o->model == WO_MODEL_VECTOR_3D) return run_vector_tf(o, n, s, (float2*)tf_out, ws, hs);
+  if (o->model == WO_MODEL_VECTOR_3D) return run_vector_tf(o, n, s, (float2*)tf_out, ws, hs, band_out);
   const int fs = field_sets(o);
   const int nv = n * fs;          // field sets: patch i, aperture c at i * fs + c
   std::vector<DevOptics> h(nv);
@@ -1588,7 +1589,8 @@ int wo_transfer_function_band(const wo_optics* o, int32_t n, void* tf_out, void*
   // comes from the compact Z pass of the label-free 3D models
   bool compact_out = false;
   const LatSupport sup = tf_support(o, n, s, &compact_out);
-  if (!compact_out && (s.thin || sup.kt < s.Xh || sup.ky < s.Y)) return WO_EUNSUPPORTED;
+  if (o->model != WO_MODEL_VECTOR_3D && !compact_out && (s.thin || sup.kt < s.Xh || sup.ky < s.Y))
+    return WO_EUNSUPPORTED;
   if (ws_bytes < tf_ws(o, n, s)) return WO_ENOMEM;
   return run_tf(o, n, s, tf_out, ws, (hipStream_t)stream, true);
 }

@@ -49,9 +49,13 @@ hipError_t launch_set_vec(VecRec* dst, const VecRec* host, int n, hipStream_t s)
 // and the map Q in FP64, then every plane's propagator phase.  Q is written
 // without angles: with w = 1 / (k_m (k_m + kz)),
 //   Q = [[1 - px^2 w, -px py w], [-px py w, 1 - py^2 w], [-px / k_m, -py / k_m]].
+// NS (1 or 5 illumination states) is a template parameter so that the
+// per-state arrays stay in registers (a runtime bound indexed them from
+// scratch memory).
+template <int NS>
 __global__ __launch_bounds__(256) void k_vec_spectra(const DevOptics* __restrict__ opt,
                                                      const VecRec* __restrict__ rec, Sampling sm,
-                                                     float2* __restrict__ fields, int NS, int XC, int KP) {
+                                                     float2* __restrict__ fields, int XC, int KP) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   const int ky = blockIdx.y;
   const long patch = blockIdx.z;
@@ -74,7 +78,7 @@ __global__ __launch_bounds__(256) void k_vec_spectra(const DevOptics* __restrict
   // u_i'n spectrum: i (P k_m / kz) Q_n,i' e^{i phi}; w_k: S P conj(e_k) e^{i phi}
   float q[3][2] = {{0.f, 0.f}, {0.f, 0.f}, {0.f, 0.f}};
   float gp = 0.f, sp = 0.f;
-  float2 ce[5][3];
+  float2 ce[NS][3];
   if (P != 0.0 && kz > 0.0) {
     const double w = 1.0 / (km * (km + kz));
     q[0][0] = (float)(1.0 - fx * fx * w);
@@ -86,6 +90,7 @@ __global__ __launch_bounds__(256) void k_vec_spectra(const DevOptics* __restrict
     gp = (float)(P * km / kz);
     sp = (float)(S * P);
   }
+#pragma unroll
   for (int s = 0; s < NS; ++s) {
     const float2 jx = make_float2(rec[patch].J[s][0][0], rec[patch].J[s][0][1]);
     const float2 jy = make_float2(rec[patch].J[s][1][0], rec[patch].J[s][1][1]);
@@ -108,6 +113,7 @@ __global__ __launch_bounds__(256) void k_vec_spectra(const DevOptics* __restrict
         const float a = gp * q[n][ip];
         pz[(long)(3 * ip + n) * Z * plane] = make_float2(-a * sn, a * cs);   // i a e^{i phi}
       }
+#pragma unroll
     for (int s = 0; s < NS; ++s)
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
@@ -124,7 +130,12 @@ hipError_t launch_vec_spectra(const DevOptics* opt, const VecRec* rec, const Sam
   if (XC < 1 || XC > sm.nx || KP < 0 || KP >= XC) return hipErrorInvalidValue;
   const dim3 grid((unsigned)((XC + 255) / 256), (unsigned)sm.ny, (unsigned)npatch);
   ScopedTiming _t("k_vec_spectra", s);
-  hipLaunchKernelGGL(k_vec_spectra, grid, dim3(256), 0, s, opt, rec, sm, fields, NS, XC, KP);
+  if (NS == 1)
+    hipLaunchKernelGGL(k_vec_spectra<1>, grid, dim3(256), 0, s, opt, rec, sm, fields, XC, KP);
+  else if (NS == 5)
+    hipLaunchKernelGGL(k_vec_spectra<5>, grid, dim3(256), 0, s, opt, rec, sm, fields, XC, KP);
+  else
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
@@ -211,28 +222,34 @@ hipError_t launch_rows_c2c(const float2* src, float2* dst, int X, int XC, int KP
 
 // One thread per voxel of one patch: beta_n = sum_i' alpha_c,i' u_i'n for
 // every channel, then 2 Re(sum_n,k T_p^{nk} beta_n conj(w_k)) / (Y X I_bg)
-// for every property.
+// for every property.  NS illumination states: one (the four Stokes channels
+// share it) or five (channel c uses state c); compile-time, so that every
+// array index is static and the fields stay in registers.
+template <int NS>
 __global__ __launch_bounds__(256) void k_vec_products(const VecRec* __restrict__ rec,
                                                       const float2* __restrict__ fields,
-                                                      float* __restrict__ out, long vox, int F) {
+                                                      float* __restrict__ out, long vox) {
+  constexpr int C = NS == 1 ? 4 : 5, F = 6 + 3 * NS;
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
   const long patch = blockIdx.y;
   if (i >= vox) return;
   const VecRec& r = rec[patch];
-  const int C = r.C, P = r.P, NS = r.NS;
+  const int P = r.P;
   const float2* fp = fields + patch * (long)F * vox + i;
-  float2 u[6], w[5][3];
+  float2 u[6], w[NS][3];
 #pragma unroll
   for (int f = 0; f < 6; ++f) u[f] = fp[(long)f * vox];
+#pragma unroll
   for (int s = 0; s < NS; ++s)
 #pragma unroll
     for (int k = 0; k < 3; ++k) w[s][k] = fp[(long)(6 + 3 * s + k) * vox];
   const float sc = 2.f * r.scale;
   float* op = out + patch * (long)C * P * vox + i;
+#pragma unroll
   for (int c = 0; c < C; ++c) {
+    const int s = NS == 1 ? 0 : c;
     const float2 a0 = make_float2(r.alpha[c][0][0], r.alpha[c][0][1]);
     const float2 a1 = make_float2(r.alpha[c][1][0], r.alpha[c][1][1]);
-    const int s = r.state[c];
     float2 qm[3][3];
 #pragma unroll
     for (int n = 0; n < 3; ++n) {
@@ -257,7 +274,12 @@ hipError_t launch_vec_products(const VecRec* rec, const float2* fields, float* o
   if (vox < 1 || npatch < 1 || npatch > 65535) return hipErrorInvalidValue;
   const dim3 grid((unsigned)((vox + 255) / 256), (unsigned)npatch);
   ScopedTiming _t("k_vec_products", s);
-  hipLaunchKernelGGL(k_vec_products, grid, dim3(256), 0, s, rec, fields, out, vox, F);
+  if (F == 9)
+    hipLaunchKernelGGL(k_vec_products<1>, grid, dim3(256), 0, s, rec, fields, out, vox);
+  else if (F == 21)
+    hipLaunchKernelGGL(k_vec_products<5>, grid, dim3(256), 0, s, rec, fields, out, vox);
+  else
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 

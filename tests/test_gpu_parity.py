@@ -143,6 +143,11 @@ CASES = {
                                        ill_jones=(0.6, 0.8j), edge_width=0.5, zernike=(0.1, 0.0, 0.05))],
     "vector_pol_states": [vector(nz=12, ny=64, nx=48, vec_channels=1, swing=0.08, defocus=-0.15,
                                  edge_width=0.5)],
+    # the vector bank's support well inside the grid (band layout, compact spectra)
+    "vector_band_batch2": [vector(nz=12, ny=96, nx=128, na_det=0.8, na_ill=0.4, vec_channels=1,
+                                  tilt_zenith=0.15, edge_width=0.5),
+                           vector(nz=12, ny=96, nx=128, na_det=0.8, na_ill=0.4, vec_channels=1, swing=0.05,
+                                  defocus=0.2, edge_width=0.5)],
 }
 
 
@@ -311,7 +316,7 @@ def band_slice(torch, full, sup, ny):
 
 
 @pytest.mark.parametrize("name", ["labelfree_3d", "labelfree_3d_band_batch2", "labelfree_3d_short_transforms",
-                                  "sectors9_band", "labelfree_3d_aberrated"])
+                                  "sectors9_band", "labelfree_3d_aberrated", "vector_band_batch2", "vector_stokes"])
 def test_band_bank_is_the_full_bank_on_its_support(gpu_lib, torch, name):
     """wo_transfer_function_band writes bit for bit the values of the full bank on
     the support; the full bank is exactly zero off it."""
@@ -329,7 +334,7 @@ def test_band_bank_is_the_full_bank_on_its_support(gpu_lib, torch, name):
 
 
 @pytest.mark.parametrize("name", ["labelfree_3d_band_batch2", "labelfree_3d_short_transforms", "sectors9_band",
-                                  "fluor_cfg1"])
+                                  "fluor_cfg1", "vector_band_batch2"])
 def test_linear_calls_with_the_band_bank_equal_the_full_bank(gpu_lib, torch, name):
     """wo_linear_band (forward, reconstruction, adjoint) with the band layout cut from
     the full bank gives bit for bit the full-layout calls' results."""
