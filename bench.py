@@ -641,7 +641,7 @@ def main():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--tune-patches", type=int, default=256)
     ap.add_argument("--tune-iters", type=int, default=100)
-    ap.add_argument("--cnn-train-patches", type=int, default=16384)
+    ap.add_argument("--cnn-train-patches", type=int, default=51200)
     ap.add_argument("--cnn-epochs", type=int, default=8)
     ap.add_argument("--cnn-tune-iters", type=int, default=20)
     ap.add_argument("--restore-tiles", type=int, default=64)
