@@ -736,6 +736,7 @@ def main():
         "lateral_support": head["lateral_support"],
         "fft_schedules": head["fft_schedules"],
         "kernels": head["kernels"],
+        "hbm_target_60pct": head["hbm_target_60pct"],
         "secondary": {SECTIONS[k]["name"]: results[k] for k in keys[1:]},
     }
 
