@@ -117,13 +117,19 @@ def kernel_bytes(name, Z, Y, X, sup, C=1, P=2, E=None, F=None):
         # forward transform on the bank's support (kt columns, band rows), whose
         # Z pass writes the full half-spectrum bank
         half_full = Z * Y * Xh
+        # the fused path works on the support's shortened transforms ly x lx
+        sl = Z * ly * sup["tf_lengths"][1]
+        rows_kt_s = Z * ly * kt
         table.update({
-            "k_vec_spectra": F * cplx * Z * Y * fb,
-            "k_cols_vec": 2 * F * cplx * Z * Y * fb,
+            "k_vec_spectra": F * cplx * Z * ly * fb,
+            "k_cols_vec": 2 * F * cplx * Z * ly * fb,
             "k_rows_c2c": F * cplx * (Z * Y * fb + full),
             "k_vec_products": F * cplx * full + C * P * 4 * full,
-            "k_rows_r2c_tf": C * P * (4 * full + cplx * rows_kt),
-            "k_cols_y_tf": C * P * cplx * (rows_kt + band),
+            # fused X pass + responses: per row and channel 9 spectra lines of fb
+            # kept columns read, P response rows of X written
+            "k_vec_rows_resp": Z * ly * C * (9 * cplx * fb + P * 4 * sup["tf_lengths"][1]),
+            "k_rows_r2c_tf": C * P * (4 * sl + cplx * rows_kt_s),
+            "k_cols_y_tf": C * P * cplx * (rows_kt_s + band),
             "k_cols_expand": C * P * cplx * (band + half_full),
             "k_cols_z_band": 2 * C * P * cplx * band,
         })
@@ -146,6 +152,7 @@ def counter_symbols(sup, Z, X, P, C, ns=None):
     zop = f"wo::k_zop<{P}, {ct}, {Z}, true>" if C == 5 and P == 4 else f"wo::k_zop<{P}, {ct}, {Z}, false>"
     if ns is not None:   # the vector bank's synthesis (ns illumination states)
         return {"k_vec_products": f"wo::k_vec_products<{ns}>", "k_vec_spectra": f"wo::k_vec_spectra<{ns}>",
+                "k_vec_rows_resp": f"wo::k_vec_rows_resp<{ns}, {X}>",
                 "k_rows_c2c": f"wo::k_rows_c2c<{X}>", f"k_zop<{P}>": f"wo::k_zop<{P}, {ct}, {Z}, false>",
                 "k_rows_r2c": f"wo::k_rows_r2c<{X}>", "k_rows_c2r": f"wo::k_rows_c2r<{X}>"}
     return {f"k_zop<{P}>": zop, "k_rows_r2c": f"wo::k_rows_r2c<{X}>",

@@ -194,12 +194,14 @@ int wo_transfer_function(const wo_optics* o, int32_t n, void* tf_out, void* ws, 
  * elsewhere, as wo_transfer_function writes it. */
 typedef struct wo_support {
   int32_t field_cols[2];  /* lateral columns the synthesis keeps of field A (or the
-                             fluorescence field) and of B (0: no second field) */
+                             fluorescence field) and of B (0: no second field); the
+                             vector model keeps every field on B's columns */
   int32_t tf_cols;        /* the bank's half-spectrum columns k < tf_cols can be nonzero */
   int32_t band_rows;      /* and its rows y <= ky or y >= ny - ky: 2 ky + 1 (ny: all) */
   int32_t tf_lengths[2];  /* (y, x) transform lengths of the synthesis: the bank is a
                              correlation of the fields' spectra, so lengths beyond its
-                             extent give it exactly; the label-free 3D models use the
+                             extent give it exactly; the label-free 3D models, and the
+                             vector model where that x length is compiled, use the
                              shortest compiled lengths that hold it, the others (ny, nx) */
 } wo_support;
 int wo_lateral_support(const wo_optics* o, int32_t n, wo_support* out);

@@ -400,8 +400,9 @@ double host_ibg(const wo_optics& oo) {
 }
 
 // Constants of one patch of the vector model (channels, property tensors,
-// normalisation); false if no direct light reaches the detector.
-bool vec_rec(const wo_optics& o, VecRec* r) {
+// normalisation on the grid and on LY x LX shortened transforms); false if no
+// direct light reaches the detector.
+bool vec_rec(const wo_optics& o, VecRec* r, int LY, int LX) {
   memset(r, 0, sizeof(*r));
   const cd I(0.0, 1.0);
   cd J[5][2];
@@ -457,6 +458,7 @@ bool vec_rec(const wo_optics& o, VecRec* r) {
   const double ibg = host_ibg(o);
   if (!(ibg > 0.0)) return false;
   r->scale = (float)(1.0 / ((double)o.ny * o.nx * ibg));
+  r->scale_short = (float)(1.0 / ((double)LY * LX * ibg));
   r->C = C;
   r->P = o.vec_nprops;
   r->NS = NS;
@@ -589,17 +591,32 @@ LatSupport tf_support(const wo_optics* o, int32_t n, const Shape& s, bool* compa
 // detection pupil's columns (later the bank's columns k < kt before its Z
 // pass), the fields on the grid (6 + 3 per illumination state each) and the
 // real channel responses.
-size_t vec_compact_elems(const wo_optics* o, int32_t n, const Shape& s, const LatSupport& sup) {
+// Transform lengths of the vector synthesis: with a compiled row length the
+// fused X pass runs on the support's shortened transforms LY x LX (they hold
+// the responses' band without wrap-around, as for the label-free bank);
+// otherwise the grid's own, through the separate X pass and products.
+struct VecLengths {
+  bool fused;
+  int LY, LX;
+};
+VecLengths vec_lengths(const Shape& s, const LatSupport& sup) {
+  if (vec_rows_fused(sup.lx)) return VecLengths{true, sup.ly, sup.lx};
+  return VecLengths{false, (int)s.Y, (int)s.X};
+}
+
+size_t vec_compact_elems(const wo_optics* o, int32_t n, const Shape& s, const LatSupport& sup, int LY) {
   const long F = 6 + 3 * (o->vec_channels == 0 ? 1 : 5);
-  return (size_t)n * s.Z * s.Y * std::max(F * sup.xc, (long)s.C * s.P * sup.kt);
+  return (size_t)n * s.Z * LY * std::max(F * sup.xc, (long)s.C * s.P * sup.kt);
 }
 
 size_t vec_ws(const wo_optics* o, int32_t n, const Shape& s) {
   const int F = 6 + 3 * (o->vec_channels == 0 ? 1 : 5);
-  const size_t vox = (size_t)s.Z * s.Y * s.X;
   const LatSupport sup = lateral_support(o, n);
+  const VecLengths L = vec_lengths(s, sup);
+  const size_t vox = (size_t)s.Z * L.LY * L.LX;
+  const size_t full_fields = L.fused ? 0 : align_up((size_t)n * F * vox * sizeof(float2));
   return params_bytes(n) + align_up((size_t)n * sizeof(VecRec)) +
-         align_up(vec_compact_elems(o, n, s, sup) * sizeof(float2)) + align_up((size_t)n * F * vox * sizeof(float2)) +
+         align_up(vec_compact_elems(o, n, s, sup, L.LY) * sizeof(float2)) + full_fields +
          align_up((size_t)n * s.C * s.P * vox * sizeof(float));
 }
 
@@ -1404,6 +1421,12 @@ int wo_lateral_support(const wo_optics* o, int32_t n, wo_support* out) {
   out->band_rows = ls.ky >= o->ny ? o->ny : 2 * ls.ky + 1;
   out->tf_lengths[0] = ts.ly;
   out->tf_lengths[1] = ts.lx;
+  if (o->model == WO_MODEL_VECTOR_3D) {   // every field on the detection pupil's columns
+    const VecLengths L = vec_lengths(s, ls);
+    out->field_cols[0] = out->field_cols[1] = ls.xc;
+    out->tf_lengths[0] = L.LY;
+    out->tf_lengths[1] = L.LX;
+  }
   return WO_OK;
 }
 
@@ -1414,40 +1437,45 @@ static int run_vector_tf(const wo_optics* o, int32_t n, const Shape& s, float2* 
                          bool band_out) {
   const int NS = o->vec_channels == 0 ? 1 : 5;
   const int F = 6 + 3 * NS;
+  const LatSupport sup = lateral_support(o, n);   // the detection pupils' columns: sup.xc, sup.kp
+  const VecLengths L = vec_lengths(s, sup);
   std::vector<DevOptics> h(n);
   std::vector<VecRec> vr(n);
   for (int i = 0; i < n; ++i) {
     h[i] = dev_optics(o[i]);
-    if (!vec_rec(o[i], &vr[i])) return WO_EINVAL;
+    if (!vec_rec(o[i], &vr[i], L.LY, L.LX)) return WO_EINVAL;
   }
-  const long vox = s.Z * s.Y * s.X;
-  const LatSupport sup = lateral_support(o, n);   // the detection pupils' columns: sup.xc, sup.kp
+  const long vox = s.Z * (long)L.LY * L.LX;
   char* w = (char*)ws;
   DevOptics* dopt = (DevOptics*)w;
   w += params_bytes(n);
   VecRec* drec = (VecRec*)w;
   w += align_up((size_t)n * sizeof(VecRec));
   float2* spec = (float2*)w;
-  w += align_up(vec_compact_elems(o, n, s, sup) * sizeof(float2));
+  w += align_up(vec_compact_elems(o, n, s, sup, L.LY) * sizeof(float2));
   float2* fields = (float2*)w;
-  w += align_up((size_t)n * F * vox * sizeof(float2));
+  if (!L.fused) w += align_up((size_t)n * F * vox * sizeof(float2));
   float* resp = (float*)w;
   WO_TRY(launch_set_params(dopt, h.data(), n, hs));
   WO_TRY(launch_set_vec(drec, vr.data(), n, hs));
   const Sampling sm = sampling_of(o);
-  WO_TRY(launch_vec_spectra(dopt, drec, sm, n, NS, spec, sup.xc, sup.kp, hs));
-  WO_TRY(launch_cols(spec, (int)s.Y, sup.xc, (long)F * s.Z, (long)F * s.Z, n, 1.f, hs, "k_cols_vec"));
-  WO_TRY(launch_rows_c2c(spec, fields, (int)s.X, sup.xc, sup.kp, (long)n * F * s.Z * s.Y, 1.f, hs));
-  WO_TRY(launch_vec_products(drec, fields, resp, vox, F, n, hs));
+  WO_TRY(launch_vec_spectra(dopt, drec, sm, n, NS, spec, sup.xc, sup.kp, L.LY, hs));
+  WO_TRY(launch_cols(spec, L.LY, sup.xc, (long)F * s.Z, (long)F * s.Z, n, 1.f, hs, "k_cols_vec"));
+  if (L.fused) {
+    WO_TRY(launch_vec_rows_resp(drec, spec, resp, L.LX, sup.xc, sup.kp, s.Z * (long)L.LY, NS, n, hs));
+  } else {
+    WO_TRY(launch_rows_c2c(spec, fields, L.LX, sup.xc, sup.kp, (long)n * F * s.Z * L.LY, 1.f, hs));
+    WO_TRY(launch_vec_products(drec, fields, resp, vox, F, n, hs));
+  }
   // the bank vanishes outside the columns k < kt and the band rows: the X and
   // Y transforms keep those (in the spectra's buffer), the Z pass writes the
   // full bank with zeros elsewhere, or the band layout (band_out)
-  const long rows = (long)s.C * s.P * s.Z * s.Y;
+  const long rows = (long)s.C * s.P * s.Z * L.LY;
   const RowGroups g{rows, rows, rows, n};
-  WO_TRY(launch_rows_r2c(resp, spec, (int)s.X, g, hs, sup.kt, sup.kt, "k_rows_r2c_tf"));
+  WO_TRY(launch_rows_r2c(resp, spec, L.LX, g, hs, sup.kt, sup.kt, "k_rows_r2c_tf"));
   const long planes = (long)s.C * s.P * s.Z;
-  WO_TRY(launch_cols(spec, (int)s.Y, sup.kt, planes, planes, n, -1.f, hs, "k_cols_y_tf", 1, sup.ky));
-  WO_TRY(launch_cols_expand(spec, tf, (int)s.Z, (int)s.Y, (int)s.Y, (int)s.Xh, sup.kt, sup.ky,
+  WO_TRY(launch_cols(spec, L.LY, sup.kt, planes, planes, n, -1.f, hs, "k_cols_y_tf", 1, sup.ky));
+  WO_TRY(launch_cols_expand(spec, tf, (int)s.Z, L.LY, (int)s.Y, (int)s.Xh, sup.kt, sup.ky,
                             (long)n * s.C * s.P, -1.f, hs, band_out));
   return WO_OK;
 }

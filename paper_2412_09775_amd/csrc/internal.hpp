@@ -256,16 +256,18 @@ struct VecRec {
   float alpha[5][2][2];
   int state[5];
   float T[8][9][2];
-  float scale;
+  float scale;         // 1 / (Y X I_bg): responses on the grid
+  float scale_short;   // 1 / (LY LX I_bg): responses on the shortened transforms
   int C, P, NS;
 };
 hipError_t launch_set_vec(VecRec* dst, const VecRec* host, int n, hipStream_t s);
 // Field spectra fields [patch][f][z][y][c] on the XC kept columns c (column kx
-// = field_column(c, KP, X, XC)): f < 6 the detected scattered field of a unit
+// = field_column(c, KP, X, XC)) and LY rows (row i the grid's frequency (i or
+// i - LY) / (ny dy)): f < 6 the detected scattered field of a unit
 // dipole, u_i'n (f = 3 i' + n), then for each illumination state s the direct
 // arm S P E conj(e_k) (f = 6 + 3 s + k), each times the propagator of plane z.
 hipError_t launch_vec_spectra(const DevOptics* opt, const VecRec* rec, const Sampling& sm, int npatch, int NS,
-                              float2* fields, int XC, int KP, hipStream_t s);
+                              float2* fields, int XC, int KP, int LY, hipStream_t s);
 // Unnormalised complex FFT along X (sign -1 forward, +1 inverse) of nrows rows:
 // src rows hold the XC kept columns (the others zero), dst rows all X values.
 hipError_t launch_rows_c2c(const float2* src, float2* dst, int X, int XC, int KP, long nrows, float sign,
@@ -274,5 +276,12 @@ hipError_t launch_rows_c2c(const float2* src, float2* dst, int X, int XC, int KP
 // transformed fields [patch][F][vox].
 hipError_t launch_vec_products(const VecRec* rec, const float2* fields, float* out, long vox, int F, int npatch,
                                hipStream_t s);
+// Whether the row length has the fused X pass + responses kernel (compiled lengths).
+bool vec_rows_fused(int X);
+// The same responses straight from the Y-transformed spectra [patch][F][zy][XC]
+// (zy = Z * Y rows of the kept columns): X inverse transforms and products
+// fused per row and channel.
+hipError_t launch_vec_rows_resp(const VecRec* rec, const float2* spec, float* out, int X, int XC, int KP, long zy,
+                                int NS, int npatch, hipStream_t s);
 
 }  // namespace wo

@@ -52,21 +52,26 @@ hipError_t launch_set_vec(VecRec* dst, const VecRec* host, int n, hipStream_t s)
 // NS (1 or 5 illumination states) is a template parameter so that the
 // per-state arrays stay in registers (a runtime bound indexed them from
 // scratch memory).
+// LY rows: row i of the LY-point transform stands for the grid's frequency
+// (i or i - LY) / (ny dy); LY = ny is the grid's own transform, a shorter one
+// (longer than twice the band) samples the same band-limited fields more
+// coarsely along y.
 template <int NS>
 __global__ __launch_bounds__(256) void k_vec_spectra(const DevOptics* __restrict__ opt,
                                                      const VecRec* __restrict__ rec, Sampling sm,
-                                                     float2* __restrict__ fields, int XC, int KP) {
+                                                     float2* __restrict__ fields, int XC, int KP, int LY) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   const int ky = blockIdx.y;
   const long patch = blockIdx.z;
-  const int X = sm.nx, Y = sm.ny, Z = sm.nz;
+  const int X = sm.nx, Z = sm.nz;
   if (c >= XC) return;
   const int kx = field_column(c, KP, X, XC);
   const DevOptics o = opt[patch];
   const int F = 6 + 3 * NS;
-  const long plane = (long)Y * XC;
+  const long plane = (long)LY * XC;
   float2* base = fields + patch * (long)F * Z * plane + (long)ky * XC + c;
-  const double fy = fftfreq(ky, Y, sm.dy), fx = fftfreq(kx, X, sm.dx);
+  const double fy = (double)(ky < (LY + 1) / 2 ? ky : ky - LY) / ((double)sm.ny * sm.dy);
+  const double fx = fftfreq(kx, X, sm.dx);
   const double hw = soft_halfwidth(o, sm);
   const double km = o.n_medium / o.wavelength;
   const DetAxis dax = det_axis(o);
@@ -125,15 +130,15 @@ __global__ __launch_bounds__(256) void k_vec_spectra(const DevOptics* __restrict
 }
 
 hipError_t launch_vec_spectra(const DevOptics* opt, const VecRec* rec, const Sampling& sm, int npatch, int NS,
-                              float2* fields, int XC, int KP, hipStream_t s) {
-  if (NS < 1 || NS > 5 || npatch < 1 || npatch > 65535 || sm.ny > 65535) return hipErrorInvalidValue;
+                              float2* fields, int XC, int KP, int LY, hipStream_t s) {
+  if (NS < 1 || NS > 5 || npatch < 1 || npatch > 65535 || LY < 2 || LY > sm.ny) return hipErrorInvalidValue;
   if (XC < 1 || XC > sm.nx || KP < 0 || KP >= XC) return hipErrorInvalidValue;
-  const dim3 grid((unsigned)((XC + 255) / 256), (unsigned)sm.ny, (unsigned)npatch);
+  const dim3 grid((unsigned)((XC + 255) / 256), (unsigned)LY, (unsigned)npatch);
   ScopedTiming _t("k_vec_spectra", s);
   if (NS == 1)
-    hipLaunchKernelGGL(k_vec_spectra<1>, grid, dim3(256), 0, s, opt, rec, sm, fields, XC, KP);
+    hipLaunchKernelGGL(k_vec_spectra<1>, grid, dim3(256), 0, s, opt, rec, sm, fields, XC, KP, LY);
   else if (NS == 5)
-    hipLaunchKernelGGL(k_vec_spectra<5>, grid, dim3(256), 0, s, opt, rec, sm, fields, XC, KP);
+    hipLaunchKernelGGL(k_vec_spectra<5>, grid, dim3(256), 0, s, opt, rec, sm, fields, XC, KP, LY);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
@@ -281,6 +286,126 @@ hipError_t launch_vec_products(const VecRec* rec, const float2* fields, float* o
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
+}
+
+// Channel responses straight from the Y-transformed spectra (compiled row
+// lengths N, the grid's X or a shorter length holding the responses'
+// band without wrap-around): one workgroup per row (patch, z, y) and channel c.  beta_n =
+// sum_i' alpha_c,i' u_i'n is linear in the fields, so its three lines are
+// formed from the u spectra as they are loaded; with the three w lines of
+// the channel's state they are inverse-transformed along X in LDS (six
+// lines), and each x then gets the channel's P responses.  This replaces the
+// full-grid fields' round trip through HBM (the X pass writing them, the
+// products reading them) by a re-read of the compact spectra per channel.
+template <int NS, int N>
+__global__ __launch_bounds__(1024) void k_vec_rows_resp(const VecRec* __restrict__ rec,
+                                                        const float2* __restrict__ spec,
+                                                        float* __restrict__ out, int XC, int KP, long zy) {
+  constexpr int C = NS == 1 ? 4 : 5, F = 6 + 3 * NS, NL = 6;
+  extern __shared__ float2 smem[];
+  float2* tw = smem;
+  float2* buf = smem + N;
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const long rowid = blockIdx.x / C;
+  const int c = (int)(blockIdx.x - rowid * C);
+  const long patch = rowid / zy, r = rowid - patch * zy;
+  const VecRec& rv = rec[patch];
+  const int s = NS == 1 ? 0 : c;
+  const float2 a0 = make_float2(rv.alpha[c][0][0], rv.alpha[c][0][1]);
+  const float2 a1 = make_float2(rv.alpha[c][1][0], rv.alpha[c][1][1]);
+  const float2* sp = spec + patch * (long)F * zy * XC + r * XC;
+  const int PS = pad_shift(N), LS = row_stride(N);
+  fill_twiddles(tw, N, tid, nthr);
+  // line l < 3: beta_l = alpha_0 u_0l + alpha_1 u_1l; l >= 3: w_{l-3} of state s
+  auto load = [&](int l, int k) {
+    const int cc = compact_column(k, KP, N, XC);
+    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (cc >= 0) {
+      if (l < 3) {
+        const float2 u0 = sp[(long)l * zy * XC + cc], u1 = sp[(long)(3 + l) * zy * XC + cc];
+        v = make_float4(u0.x, u0.y, u1.x, u1.y);
+      } else {
+        const float2 w = sp[(long)(6 + 3 * s + l - 3) * zy * XC + cc];
+        v = make_float4(w.x, w.y, 0.f, 0.f);
+      }
+    }
+    return v;
+  };
+  auto finish = [&](int l, int, float4 v) {
+    if (l >= 3) return make_float2(v.x, v.y);
+    return cadd(cmul(a0, make_float2(v.x, v.y)), cmul(a1, make_float2(v.z, v.w)));
+  };
+  constexpr int NP = StaticPlan<N>::passes();
+  first_pass_in2<N, 0, false, kEmax, true, false>(buf, NL, 1, LS, -1, 1.f, tid, nthr, load, finish, [] {});
+  static_passes<N, 0, false, kEmax, true, false, 1, NP>(buf, NL, 1, LS, -1, tw, 1.f, tid, nthr);
+  __syncthreads();
+  const int P = rv.P;
+  const float sc = 2.f * rv.scale_short;
+  const long vox = zy * N;
+  float* op = out + (patch * (long)C + c) * P * vox + r * N;
+  for (int x = tid; x < N; x += nthr) {
+    const int sl = row_slot(x, PS);
+    float2 qm[3][3];
+#pragma unroll
+    for (int n = 0; n < 3; ++n) {
+      const float2 b = buf[n * LS + sl];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const float2 w = buf[(3 + k) * LS + sl];
+        qm[n][k] = cmul(b, make_float2(w.x, -w.y));
+      }
+    }
+    for (int p = 0; p < P; ++p) {
+      float acc = 0.f;
+#pragma unroll
+      for (int e = 0; e < 9; ++e) {
+        const float2 t = make_float2(rv.T[p][e][0], rv.T[p][e][1]);
+        acc += t.x * qm[e / 3][e % 3].x - t.y * qm[e / 3][e % 3].y;
+      }
+      op[(long)p * vox + x] = sc * acc;
+    }
+  }
+}
+
+bool vec_rows_fused(int X) {
+  switch (X) {
+#define X_(NN) case NN:
+    WO_LATERAL_SIZES(X_)
+#undef X_
+    return true;
+    default:
+      return false;
+  }
+}
+
+hipError_t launch_vec_rows_resp(const VecRec* rec, const float2* spec, float* out, int X, int XC, int KP, long zy,
+                                int NS, int npatch, hipStream_t s) {
+  if (!vec_rows_fused(X) || (NS != 1 && NS != 5) || zy < 1 || npatch < 1 || XC < 1 || XC > X || KP < 0 ||
+      KP >= XC)
+    return hipErrorInvalidValue;
+  const int C = NS == 1 ? 4 : 5;
+  const long nwg = (long)npatch * zy * C;
+  if (nwg > 0x7fffffffL) return hipErrorInvalidValue;
+  const int thr = threads_for(6L * X);
+  const size_t lds = (size_t)(X + 6L * row_stride(X)) * sizeof(float2);
+  if ((long)lds > lds_limit_bytes()) return hipErrorInvalidValue;
+  ScopedTiming _t("k_vec_rows_resp", s);
+#define X_(NN)                                                                                       \
+  case NN:                                                                                           \
+    if (NS == 1)                                                                                     \
+      hipLaunchKernelGGL((k_vec_rows_resp<1, NN>), dim3((unsigned)nwg), dim3(thr), lds, s, rec, spec, out, XC, \
+                         KP, zy);                                                                    \
+    else                                                                                             \
+      hipLaunchKernelGGL((k_vec_rows_resp<5, NN>), dim3((unsigned)nwg), dim3(thr), lds, s, rec, spec, out, XC, \
+                         KP, zy);                                                                    \
+    return hipGetLastError();
+  switch (X) {
+    WO_LATERAL_SIZES(X_)
+    default:
+      break;
+  }
+#undef X_
+  return hipErrorInvalidValue;
 }
 
 }  // namespace wo
