@@ -125,9 +125,9 @@ def kernel_bytes(name, Z, Y, X, sup, C=1, P=2, E=None, F=None):
             "k_cols_vec": 2 * F * cplx * Z * ly * fb,
             "k_rows_c2c": F * cplx * (Z * Y * fb + full),
             "k_vec_products": F * cplx * full + C * P * 4 * full,
-            # fused X pass + responses: per row and channel 9 spectra lines of fb
-            # kept columns read, P response rows of X written
-            "k_vec_rows_resp": Z * ly * C * (9 * cplx * fb + P * 4 * sup["tf_lengths"][1]),
+            # fused X pass + responses: per row the F spectra lines of fb kept
+            # columns read once, C P response rows of lx written
+            "k_vec_rows_resp": Z * ly * (F * cplx * fb + C * P * 4 * sup["tf_lengths"][1]),
             "k_rows_r2c_tf": C * P * (4 * sl + cplx * rows_kt_s),
             "k_cols_y_tf": C * P * cplx * (rows_kt_s + band),
             "k_cols_expand": C * P * cplx * (band + half_full),

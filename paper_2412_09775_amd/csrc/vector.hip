@@ -19,6 +19,8 @@
 // (row passes below, zeros for the other columns), multiplied per voxel, and
 // the real responses transformed forward by the row and column passes of the
 // linear model.
+#include <algorithm>
+
 #include "internal.hpp"
 
 namespace wo {
@@ -367,6 +369,85 @@ __global__ __launch_bounds__(1024) void k_vec_rows_resp(const VecRec* __restrict
   }
 }
 
+// The same for every channel of a row in one workgroup, where the row's six u
+// lines and 3 NS w lines fit LDS (each set transformed in one batch): the
+// spectra are read once per row instead of once per channel, and beta is
+// formed per x from the transformed u lines.
+template <int NS, int N>
+__global__ __launch_bounds__(1024) void k_vec_rows_all(const VecRec* __restrict__ rec,
+                                                       const float2* __restrict__ spec,
+                                                       float* __restrict__ out, int XC, int KP, long zy) {
+  constexpr int C = NS == 1 ? 4 : 5, F = 6 + 3 * NS, NW = 3 * NS;
+  extern __shared__ float2 smem[];
+  float2* tw = smem;
+  const int LS = row_stride(N), PS = pad_shift(N);
+  float2* bu = smem + N;            // 6 u lines
+  float2* bw = bu + 6 * LS;         // 3 NS w lines
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const long rowid = blockIdx.x;
+  const long patch = rowid / zy, r = rowid - patch * zy;
+  const VecRec& rv = rec[patch];
+  const float2* sp = spec + patch * (long)F * zy * XC + r * XC;
+  fill_twiddles(tw, N, tid, nthr);
+  auto finish = [](int, int, float2 v) { return v; };
+  constexpr int NP = StaticPlan<N>::passes();
+  auto load_u = [&](int l, int k) {
+    const int cc = compact_column(k, KP, N, XC);
+    return cc >= 0 ? sp[(long)l * zy * XC + cc] : make_float2(0.f, 0.f);
+  };
+  auto load_w = [&](int l, int k) {
+    const int cc = compact_column(k, KP, N, XC);
+    return cc >= 0 ? sp[(long)(6 + l) * zy * XC + cc] : make_float2(0.f, 0.f);
+  };
+  first_pass_in2<N, 0, false, kEmax, true, false>(bu, 6, 1, LS, -1, 1.f, tid, nthr, load_u, finish, [] {});
+  static_passes<N, 0, false, kEmax, true, false, 1, NP>(bu, 6, 1, LS, -1, tw, 1.f, tid, nthr);
+  first_pass_in2<N, 0, false, kEmax, true, false>(bw, NW, 1, LS, -1, 1.f, tid, nthr, load_w, finish, [] {});
+  static_passes<N, 0, false, kEmax, true, false, 1, NP>(bw, NW, 1, LS, -1, tw, 1.f, tid, nthr);
+  __syncthreads();
+  const int P = rv.P;
+  const float sc = 2.f * rv.scale_short;
+  const long vox = zy * N;
+  float* op = out + patch * (long)C * P * vox + r * N;
+  // one (channel, x) pair per thread and step: every thread busy, x contiguous
+  // across a wave for the stores
+  for (int e = tid; e < C * N; e += nthr) {
+    const int c = e / N, x = e - c * N;
+    const int sl = row_slot(x, PS);
+    const int s = NS == 1 ? 0 : c;
+    const float2 a0 = make_float2(rv.alpha[c][0][0], rv.alpha[c][0][1]);
+    const float2 a1 = make_float2(rv.alpha[c][1][0], rv.alpha[c][1][1]);
+    float2 cw[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const float2 w = bw[(3 * s + k) * LS + sl];
+      cw[k] = make_float2(w.x, -w.y);
+    }
+    float2 qm[3][3];
+#pragma unroll
+    for (int n = 0; n < 3; ++n) {
+      const float2 b = cadd(cmul(a0, bu[n * LS + sl]), cmul(a1, bu[(3 + n) * LS + sl]));
+#pragma unroll
+      for (int k = 0; k < 3; ++k) qm[n][k] = cmul(b, cw[k]);
+    }
+    for (int p = 0; p < P; ++p) {
+      float acc = 0.f;
+#pragma unroll
+      for (int q = 0; q < 9; ++q) {
+        const float2 t = make_float2(rv.T[p][q][0], rv.T[p][q][1]);
+        acc += t.x * qm[q / 3][q % 3].x - t.y * qm[q / 3][q % 3].y;
+      }
+      op[(long)(c * P + p) * vox + x] = sc * acc;
+    }
+  }
+}
+
+// Whether every channel of a row fits one workgroup of k_vec_rows_all.
+static bool vec_rows_all_fits(int X, int NS) {
+  const long nw = 3L * NS * X;
+  return 6L * X <= kMaxElems && nw <= kMaxElems &&
+         (long)(X + (6L + 3L * NS) * row_stride(X)) * (long)sizeof(float2) <= lds_limit_bytes();
+}
+
 bool vec_rows_fused(int X) {
   switch (X) {
 #define X_(NN) case NN:
@@ -384,6 +465,29 @@ hipError_t launch_vec_rows_resp(const VecRec* rec, const float2* spec, float* ou
       KP >= XC)
     return hipErrorInvalidValue;
   const int C = NS == 1 ? 4 : 5;
+  if (vec_rows_all_fits(X, NS)) {
+    const long nwg = (long)npatch * zy;
+    if (nwg > 0x7fffffffL) return hipErrorInvalidValue;
+    const int thr = threads_for(std::max(6L, 3L * NS) * X);
+    const size_t lds = (size_t)(X + (6L + 3L * NS) * row_stride(X)) * sizeof(float2);
+    ScopedTiming _t("k_vec_rows_resp", s);
+#define X_(NN)                                                                                       \
+  case NN:                                                                                           \
+    if (NS == 1)                                                                                     \
+      hipLaunchKernelGGL((k_vec_rows_all<1, NN>), dim3((unsigned)nwg), dim3(thr), lds, s, rec, spec, out, XC, \
+                         KP, zy);                                                                    \
+    else                                                                                             \
+      hipLaunchKernelGGL((k_vec_rows_all<5, NN>), dim3((unsigned)nwg), dim3(thr), lds, s, rec, spec, out, XC, \
+                         KP, zy);                                                                    \
+    return hipGetLastError();
+    switch (X) {
+      WO_LATERAL_SIZES(X_)
+      default:
+        break;
+    }
+#undef X_
+    return hipErrorInvalidValue;
+  }
   const long nwg = (long)npatch * zy * C;
   if (nwg > 0x7fffffffL) return hipErrorInvalidValue;
   const int thr = threads_for(6L * X);
