@@ -14,11 +14,13 @@
 //   R_cp = 1 / (Y X I_bg) sum_n,k beta_n T_p^{nk} conj(w_k),
 //   beta_n = sum_i' alpha_c,i' u_i'n,  alpha_c = J_s^H M_c,
 // and H_cp = FFT3(2 Re R_cp).  The spectra vanish outside the detection
-// pupil's columns: they are written on those columns only, inverse-
-// transformed along Y there (column passes), then along X into full rows
-// (row passes below, zeros for the other columns), multiplied per voxel, and
-// the real responses transformed forward by the row and column passes of the
-// linear model.
+// pupil's columns: they are written on those columns only and inverse-
+// transformed along Y there (column passes).  With a compiled row length the
+// X transform and the products are fused per row (k_vec_rows_all or
+// k_vec_rows_resp) on the support's shortened transforms; otherwise a complex
+// row pass writes the fields on the grid and k_vec_products multiplies them
+// per voxel.  The real responses are transformed forward by the row and
+// column passes of the linear model, on the bank's support.
 #include <algorithm>
 
 #include "internal.hpp"
