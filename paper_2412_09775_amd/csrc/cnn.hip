@@ -495,22 +495,43 @@ struct DgradClasses {
   long M[8], K[8];
 };
 
+// blockIdx.z = split * nc + class; with splits > 1 split q of every class's K
+// range writes its partial sums to out + q * Mout * N (summed afterwards in a
+// fixed order), each output row exactly once per split.
 template <int TM, int TN, int AM, int BM>
 __global__ __launch_bounds__(256) void k_gemm_dgrad(DgradClasses cl, float* __restrict__ out, long N,
-                                                    long Mout) {
-  const int c = (int)blockIdx.z;
+                                                    long Mout, int nc, int splits) {
+  const int c = (int)(blockIdx.z % nc), q = (int)(blockIdx.z / nc);
   const long m0 = (long)blockIdx.x * TM;
   if (m0 >= cl.M[c]) return;
+  long kchunk = (cl.K[c] + splits - 1) / splits;
+  kchunk = (kchunk + kBK - 1) / kBK * kBK;
+  const long kbeg = min(cl.K[c], (long)q * kchunk), kend = min(cl.K[c], kbeg + kchunk);
   gemm_tile<TM, TN, GatherCol2imClass, GatherWTClass, ClassRows, StoreC, AM, BM>(
-      cl.a[c], cl.b[c], ClassRows{cl.a[c]}, StoreC{out, Mout, N}, 0, cl.M[c], N, 0, cl.K[c], m0,
-      (long)blockIdx.y * TN);
+      cl.a[c], cl.b[c], ClassRows{cl.a[c]}, StoreC{out + (long)q * Mout * N, Mout, N}, 0, cl.M[c], N, kbeg,
+      kend, m0, (long)blockIdx.y * TN);
 }
 
-static hipError_t dgrad_classes(const u16* gz, const u16* w, ConvGeom gout, int Cin, int N,
-                                float* out, hipStream_t s) {
+// Split-K count of an input gradient: only when its tiles (over all parity
+// classes) cannot fill the GPU, up to 8 chunks of at least 256 K indices.
+static int dgrad_splits(long tiles, long kmax) {
+  if (tiles >= 1024) return 1;
+  return (int)std::max<long>(1, std::min<long>({8, (2048 + tiles - 1) / tiles, kmax / 256}));
+}
+
+// The parity classes of an input gradient (nc of them, the longest M and K,
+// and the tile count at the tile shape gemm_ep would take).
+struct DgradPlan {
   DgradClasses cl;
   int nc = 0;
-  long mmax = 0;
+  long mmax = 0, kmax = 0, tiles = 0;
+  bool narrow = false;
+};
+
+static DgradPlan dgrad_plan(const u16* gz, const u16* w, ConvGeom gout, int Cin, int N) {
+  DgradPlan pl;
+  DgradClasses& cl = pl.cl;
+  int& nc = pl.nc;
   for (int cls = 0; cls < 8; ++cls) {
     GatherCol2imClass a;
     a.gz = gz;
@@ -523,30 +544,58 @@ static hipError_t dgrad_classes(const u16* gz, const u16* w, ConvGeom gout, int 
     cl.b[nc] = GatherWTClass{w, Cin, gout.C, a.nd, a.nh, a.nw};
     cl.M[nc] = (long)N * a.cd * a.ch * a.cw;
     cl.K[nc] = (long)a.nd * a.nh * a.nw * gout.C;
-    mmax = std::max(mmax, cl.M[nc]);
+    pl.mmax = std::max(pl.mmax, cl.M[nc]);
     ++nc;
   }
+  pl.narrow = Cin <= 32;   // 128 x 32 tiles, as in gemm_ep
+  const long tm = pl.narrow ? 128 : kBM, tn = pl.narrow ? 32 : kBN;
+  for (int c = 0; c < nc; ++c) {
+    pl.tiles += ((cl.M[c] + tm - 1) / tm) * ((Cin + tn - 1) / tn);
+    pl.kmax = std::max(pl.kmax, cl.K[c]);
+  }
+  return pl;
+}
+
+static hipError_t reduce_parts(const float* part, int z, long n, float* out, hipStream_t s);
+
+// Input gradient into out (Mout x Cin): directly, or (part not null, few
+// tiles) split over K into the partials in part and summed in a fixed order.
+static hipError_t dgrad_classes(const u16* gz, const u16* w, ConvGeom gout, int Cin, int N,
+                                float* out, float* part, hipStream_t s, const char* tag = "k_gemm_conv_dgrad") {
+  const DgradPlan pl = dgrad_plan(gz, w, gout, Cin, N);
+  const DgradClasses& cl = pl.cl;
+  const int nc = pl.nc;
+  const long mmax = pl.mmax;
   if (nc == 0) return hipSuccess;
   const long Mout = (long)N * gout.D * gout.H * gout.W;
   if (Mout >= (1L << 31)) return hipErrorInvalidValue;   // 32-bit position arithmetic
-  const bool narrow = Cin <= 32;   // 128 x 32 tiles, as in gemm_ep
+  const bool narrow = pl.narrow;
   const long tm = narrow ? 128 : kBM, tn = narrow ? 32 : kBN;
-  dim3 grid((unsigned)((mmax + tm - 1) / tm), (unsigned)((Cin + tn - 1) / tn), (unsigned)nc);
+  const int splits = part ? dgrad_splits(pl.tiles, pl.kmax) : 1;
+  float* dst = splits > 1 ? part : out;
+  dim3 grid((unsigned)((mmax + tm - 1) / tm), (unsigned)((Cin + tn - 1) / tn), (unsigned)(nc * splits));
   const int am = load_mode(cl.a[0]), bm = load_mode(cl.b[0]);
-  ScopedTiming _t("k_gemm_conv_dgrad", s);
+  {
+  ScopedTiming _t(tag, s);
 #define WO_DG(A_, B_)                                                                                  \
   do {                                                                                                 \
     if (narrow)                                                                                        \
-      hipLaunchKernelGGL((k_gemm_dgrad<128, 32, A_, B_>), grid, dim3(256), 0, s, cl, out, (long)Cin, Mout); \
+      hipLaunchKernelGGL((k_gemm_dgrad<128, 32, A_, B_>), grid, dim3(256), 0, s, cl, dst, (long)Cin, Mout, nc, \
+                         splits);                                                                      \
     else                                                                                               \
-      hipLaunchKernelGGL((k_gemm_dgrad<kBM, kBN, A_, B_>), grid, dim3(256), 0, s, cl, out, (long)Cin, Mout); \
+      hipLaunchKernelGGL((k_gemm_dgrad<kBM, kBN, A_, B_>), grid, dim3(256), 0, s, cl, dst, (long)Cin, Mout, nc, \
+                         splits);                                                                      \
   } while (0)
   if (am && bm) WO_DG(GatherCol2imClass::kMode, GatherWTClass::kMode);
   else if (am) WO_DG(GatherCol2imClass::kMode, 0);
   else if (bm) WO_DG(0, GatherWTClass::kMode);
   else WO_DG(0, 0);
 #undef WO_DG
-  return hipGetLastError();
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || splits == 1) return e;
+  ScopedTiming _t("k_reduce_parts", s);
+  return reduce_parts(part, splits, Mout * Cin, out, s);
 }
 
 static int splits_used(long K, int splits) {
@@ -888,6 +937,12 @@ static CnnWs cnn_ws(const Net& net) {
     maxpart = std::max(maxpart, (long)kBiasPartsMax * L.Cout);
     const long kf = 27L * L.Cin;
     maxpart = std::max(maxpart, (long)splits_used(kf, fwd_splits(L.P_out, L.Cout, kf)) * L.P_out * L.Cout);
+    if (l > 0) {   // the input gradient's split-K partials
+      ConvGeom gd = L.g;
+      gd.C = L.Cout;
+      const DgradPlan pl = dgrad_plan(nullptr, nullptr, gd, L.Cin, net.N);
+      if (pl.nc > 0) maxpart = std::max(maxpart, (long)dgrad_splits(pl.tiles, pl.kmax) * L.P_in * L.Cin);
+    }
   }
   w.gz = take(maxg * sizeof(u16));
   w.ga = take(maxc * sizeof(float));
@@ -905,6 +960,14 @@ size_t cnn_workspace_size(int N, int Z, int Y, int X) { return cnn_ws(make_net(N
 // Forward through the convolutions (and, with targets, the backward pass that
 // fills the flat FP32 gradient).  params: FP32 flat; the BF16 copy of the
 // weights is refreshed from it at the start.
+// Timing tags of the GEMMs per layer (the library's per-kernel report).
+static const char* const kFwdTag[kCnnLayers] = {"k_gemm_conv_fwd_l0", "k_gemm_conv_fwd_l1", "k_gemm_conv_fwd_l2",
+                                                "k_gemm_conv_fwd_l3"};
+static const char* const kWgradTag[kCnnLayers] = {"k_gemm_conv_wgrad_l0", "k_gemm_conv_wgrad_l1",
+                                                  "k_gemm_conv_wgrad_l2", "k_gemm_conv_wgrad_l3"};
+static const char* const kDgradTag[kCnnLayers] = {"k_gemm_conv_dgrad_l0", "k_gemm_conv_dgrad_l1",
+                                                  "k_gemm_conv_dgrad_l2", "k_gemm_conv_dgrad_l3"};
+
 int cnn_run(const float* params, const float* x, int N, int Z, int Y, int X, const float* target,
             float* y_out, float* loss_out, float* grad_out, void* ws, hipStream_t s) {
   const Net net = make_net(N, Z, Y, X);
@@ -943,11 +1006,11 @@ int cnn_run(const float* params, const float* x, int N, int Z, int Y, int X, con
       // the GEMM's epilogue adds the bias and applies GELU (z and a written directly)
       WO_HIP_CHECK(gemm_ep(GatherIm2col{a_in, L.g}, GatherRows{pbf + L.w_off, K, L.Cin},
                            StoreBiasGelu{z, a, params + L.b_off, L.Cout}, L.P_out, L.Cout, K, 1, s,
-                           "k_gemm_conv_fwd"));
+                           kFwdTag[l]));
     } else {
       // few tiles: split K, sum the partials in a fixed order into z, then bias and GELU
       WO_HIP_CHECK(gemm(GatherIm2col{a_in, L.g}, GatherRows{pbf + L.w_off, K, L.Cin}, part, L.P_out, L.Cout,
-                        K, fs, s, "k_gemm_conv_fwd"));
+                        K, fs, s, kFwdTag[l]));
       { ScopedTiming _tm("k_reduce_parts", s);
       WO_HIP_CHECK(reduce_parts(part, splits_used(K, fs), L.P_out * L.Cout, z, s));
       }
@@ -986,14 +1049,14 @@ int cnn_run(const float* params, const float* x, int N, int Z, int Y, int X, con
     const int splits = wgrad_splits(L.P_out, L.Cout, K);
     const int zs = splits_used(L.P_out, splits);
     WO_HIP_CHECK(gemm(GatherT{gz, L.Cout}, GatherIm2colT{GatherIm2col{a_prev, L.g}}, part, L.Cout, K,
-                      L.P_out, splits, s, "k_gemm_conv_wgrad"));
+                      L.P_out, splits, s, kWgradTag[l]));
     { ScopedTiming _tm("k_reduce_parts", s);
     WO_HIP_CHECK(reduce_parts(part, zs, (long)L.Cout * K, grad + L.w_off, s));
     }
     if (l > 0) {
       ConvGeom gd = L.g;
       gd.C = L.Cout;
-      WO_HIP_CHECK(dgrad_classes(gz, pbf + L.w_off, gd, L.Cin, net.N, ga, s));
+      WO_HIP_CHECK(dgrad_classes(gz, pbf + L.w_off, gd, L.Cin, net.N, ga, part, s, kDgradTag[l]));
     }
   }
   return WO_OK;
@@ -1025,7 +1088,7 @@ hipError_t conv_fwd_raw(const u16* x, const u16* w, int N, int D, int H, int W, 
 hipError_t conv_dgrad_raw(const u16* gz, const u16* w, int N, int D, int H, int W, int Cin, int Cout,
                           float* out, hipStream_t s) {
   ConvGeom g{D, H, W, Cout, (D - 1) / 2 + 1, (H - 1) / 2 + 1, (W - 1) / 2 + 1};
-  return dgrad_classes(gz, w, g, Cin, N, out, s);
+  return dgrad_classes(gz, w, g, Cin, N, out, nullptr, s);
 }
 
 hipError_t conv_wgrad_raw(const u16* x, const u16* gz, int N, int D, int H, int W, int Cin, int Cout,
