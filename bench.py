@@ -697,7 +697,7 @@ def main():
             sys.stdout.write(text)
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus above 1 is not supported"}))
+        print(json.dumps({"error": "one GPU only: the path is not sharded across GPUs; --gpus above 1 is not supported"}))
         sys.exit(2)
 
     import torch
