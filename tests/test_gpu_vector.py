@@ -70,3 +70,35 @@ def test_vector_bank_approaches_the_polarisation_bank_at_low_na(gpu_lib):
         print(f"  scale {s}: rel diff {d:.3e}", flush=True)
         diffs.append(d)
     assert diffs[0] > 0.05 and diffs[1] < 0.02
+
+
+def test_tuned_schedules_keep_the_vector_bank_and_reconstruction(gpu_lib):
+    """The FFT tuner on the vector synthesis and on a reconstruction with the vector
+    bank (band layout): the tuned calls still match the oracle."""
+    import torch
+    from oracle import linear
+    o = vopt(nz=12, ny=96, nx=128, na_det=0.8, na_ill=0.4, vec_channels=vec.POL_STATES, vec_props=(0, 16, 8, 1),
+             tilt_zenith=0.1, edge_width=0.5)
+    print("[case] vector tf + reconstruction, tuned schedules", flush=True)
+    bank = vec.vector_3d(o)
+    rng = np.random.default_rng(9)
+    f = rng.standard_normal((4, o.nz, o.ny, o.nx)) * 0.1
+    d = linear.forward(bank, f).astype(np.float32)
+    eta = 1e-3 * linear.max_singular_value_sq(bank)
+    dt = torch.from_numpy(d[None]).cuda()
+    try:
+        tfb = gpu_lib.transfer_function_band([o])
+        gpu_lib.fft_tune(gpu_lib.OP_TRANSFER_FUNCTION, [o], out=tfb, reps=2, band=True)
+        out = torch.empty((1, 4, o.nz, o.ny, o.nx), dtype=torch.float32, device="cuda")
+        gpu_lib.fft_tune(gpu_lib.OP_RECONSTRUCT, [o], tf=tfb, x=dt, out=out, eta=eta, reps=2, band=True)
+        tf = gpu_lib.transfer_function([o]).cpu().numpy()[0]
+        tfb = gpu_lib.transfer_function_band([o])
+        rec = gpu_lib.linear_band(gpu_lib.OP_RECONSTRUCT, [o], tfb, dt, eta).cpu().numpy()[0]
+    finally:
+        gpu_lib.fft_plans_clear()
+    half = bank[..., : o.nx // 2 + 1]
+    e_tf = np.linalg.norm(tf - half) / np.linalg.norm(half)
+    ref = linear.reconstruct(bank, d, None, eta)
+    e_rec = np.linalg.norm(rec - ref) / np.linalg.norm(ref)
+    print(f"  tf {e_tf:.2e}  reconstruct {e_rec:.2e}", flush=True)
+    assert e_tf < 1e-5 and e_rec < 1e-4
