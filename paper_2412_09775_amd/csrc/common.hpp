@@ -163,6 +163,41 @@ __device__ __forceinline__ void dft6(float2* v, float s) {
   v[5] = csub(e[2], t2);
 }
 
+// 16 = 4 x 4: with n = 4 n1 + n2 and k = k1 + 4 k2, Y_n2[k1] = DFT4 over n1 of
+// v[4 n1 + n2] times W16^(n2 k1), and X[k1 + 4 k2] = DFT4 over n2 of Y_n2[k1]
+// (W16 = exp(s 2 pi i / 16); the products n2 k1 are 1, 2, 3, 4, 6 and 9).
+__device__ __forceinline__ void dft16(float2* v, float s) {
+  const float c1 = 0.92387953251128675613f;   // cos(pi / 8)
+  const float s1 = 0.38268343236508977173f;   // sin(pi / 8)
+  const float r = 0.70710678118654752440f;
+  auto rot = [](float2 x, float c, float sn) {   // x (c + i sn)
+    return make_float2(c * x.x - sn * x.y, c * x.y + sn * x.x);
+  };
+  float2 y[4][4];
+#pragma unroll
+  for (int n2 = 0; n2 < 4; ++n2) {
+#pragma unroll
+    for (int n1 = 0; n1 < 4; ++n1) y[n2][n1] = v[4 * n1 + n2];
+    dft4(y[n2], s);
+  }
+  y[1][1] = rot(y[1][1], c1, s * s1);     // W^1
+  y[1][2] = rot(y[1][2], r, s * r);       // W^2
+  y[1][3] = rot(y[1][3], s1, s * c1);     // W^3
+  y[2][1] = rot(y[2][1], r, s * r);       // W^2
+  y[2][2] = ctimes_i(y[2][2], s);         // W^4
+  y[2][3] = rot(y[2][3], -r, s * r);      // W^6
+  y[3][1] = rot(y[3][1], s1, s * c1);     // W^3
+  y[3][2] = rot(y[3][2], -r, s * r);      // W^6
+  y[3][3] = rot(y[3][3], -c1, -s * s1);   // W^9
+#pragma unroll
+  for (int k1 = 0; k1 < 4; ++k1) {
+    float2 z[4] = {y[0][k1], y[1][k1], y[2][k1], y[3][k1]};
+    dft4(z, s);
+#pragma unroll
+    for (int k2 = 0; k2 < 4; ++k2) v[k1 + 4 * k2] = z[k2];
+  }
+}
+
 template <int R>
 __device__ __forceinline__ void dft_small(float2* v, float s) {
   if constexpr (R == 2) dft2(v);
@@ -171,7 +206,77 @@ __device__ __forceinline__ void dft_small(float2* v, float s) {
   else if constexpr (R == 5) dft5(v, s);
   else if constexpr (R == 6) dft6(v, s);
   else if constexpr (R == 8) dft8(v, s);
+  else if constexpr (R == 16) dft16(v, s);
 }
+
+// Twiddle tables of the compiled transform lengths, evaluated by the compiler:
+// tw_n[m] = exp(-2 pi i m / n) rounded to FP32 from FP64 Taylor sums of sin
+// and cos on [0, pi/4] (error below 1e-16 there), the other octants by the
+// symmetries of compute_twiddles below.  A workgroup copies its table from
+// memory (it stays in the caches) instead of evaluating n/8 + 1 FP64 sines
+// and cosines.
+struct TwPair {
+  float c, s;
+};
+constexpr int kTwSizes[] = {16, 24, 32, 48, 64, 96, 128, 160, 192, 240, 256, 320, 384, 480, 512, 1024};
+constexpr int kTwCount = sizeof(kTwSizes) / sizeof(kTwSizes[0]);
+constexpr int tw_offset(int n) {
+  int off = 0;
+  for (int i = 0; i < kTwCount; ++i) {
+    if (kTwSizes[i] == n) return off;
+    off += kTwSizes[i];
+  }
+  return -1;
+}
+constexpr int kTwTotal = [] {
+  int t = 0;
+  for (int i = 0; i < kTwCount; ++i) t += kTwSizes[i];
+  return t;
+}();
+constexpr double cx_sin(double x) {   // |x| <= pi/4: terms to x^29
+  double x2 = x * x, term = x, sum = x;
+  for (int k = 1; k < 15; ++k) {
+    term *= -x2 / (double)((2 * k) * (2 * k + 1));
+    sum += term;
+  }
+  return sum;
+}
+constexpr double cx_cos(double x) {
+  double x2 = x * x, term = 1.0, sum = 1.0;
+  for (int k = 1; k < 15; ++k) {
+    term *= -x2 / (double)((2 * k - 1) * (2 * k));
+    sum += term;
+  }
+  return sum;
+}
+struct TwTables {
+  TwPair v[kTwTotal];
+};
+constexpr TwTables make_tw_tables() {
+  TwTables t{};
+  int off = 0;
+  for (int i = 0; i < kTwCount; ++i) {
+    const int n = kTwSizes[i], e = n >> 3, qn = n >> 2;
+    TwPair* tw = t.v + off;
+    for (int r = 0; r <= e; ++r) {
+      const double a = 2.0 * 3.14159265358979323846 * (double)r / (double)n;
+      const float c = (float)cx_cos(a), s = (float)cx_sin(a);
+      tw[r] = TwPair{c, -s};
+      tw[qn + r] = TwPair{-s, -c};
+      tw[2 * qn + r] = TwPair{-c, s};
+      tw[3 * qn + r] = TwPair{s, c};
+      if (r > 0 && r < e) {
+        tw[qn - r] = TwPair{s, -c};
+        tw[2 * qn - r] = TwPair{-c, -s};
+        tw[3 * qn - r] = TwPair{-s, c};
+        tw[n - r] = TwPair{c, s};
+      }
+    }
+    off += n;
+  }
+  return t;
+}
+static __device__ const TwTables kTwTables = make_tw_tables();
 
 // Twiddles tw[m] = exp(-2 pi i m / n), m < n, from FP64 sines and cosines.
 // When 8 divides n only the angles a = 2 pi r / n in [0, pi/4] (r <= n/8) are
@@ -179,7 +284,7 @@ __device__ __forceinline__ void dft_small(float2* v, float s) {
 // q pi/2 - a (q = 0..3, 1..4) have cos and sin equal to c and s up to swaps
 // and signs, so each evaluation fills up to eight entries exactly, and a
 // workgroup computes n/8 + 1 sine-cosine pairs instead of n.
-__device__ __forceinline__ void fill_twiddles(float2* tw, int n, int tid, int nthr) {
+__device__ __forceinline__ void compute_twiddles(float2* tw, int n, int tid, int nthr) {
   if ((n & 7) != 0) {
     for (int m = tid; m < n; m += nthr) {
       double sn, cs;
@@ -205,6 +310,48 @@ __device__ __forceinline__ void fill_twiddles(float2* tw, int n, int tid, int nt
       tw[n - r] = make_float2(c, s);
     }
   }
+}
+
+// The table copy in two steps, so that a kernel can issue its data loads in
+// between and the two wait on memory together: tw_begin issues this thread's
+// loads of the table of length n (at most kTwFetch entries a thread), or
+// evaluates the twiddles when n has no table or the workgroup is too small;
+// tw_end writes the fetched entries to LDS.
+constexpr int kTwFetch = 4;
+struct TwFetch {
+  float2 v[kTwFetch];
+  bool fetched;
+};
+__device__ __forceinline__ void tw_begin(TwFetch& f, float2* tw, int n, int tid, int nthr) {
+  const int off = tw_offset(n);
+  f.fetched = off >= 0 && n <= kTwFetch * nthr;
+  if (!f.fetched) {
+    compute_twiddles(tw, n, tid, nthr);
+    return;
+  }
+#pragma unroll
+  for (int i = 0; i < kTwFetch; ++i) {
+    const int m = tid + i * nthr;
+    if (m < n) {
+      const TwPair p = kTwTables.v[off + m];
+      f.v[i] = make_float2(p.c, p.s);
+    }
+  }
+}
+__device__ __forceinline__ void tw_end(const TwFetch& f, float2* tw, int n, int tid, int nthr) {
+  if (!f.fetched) return;
+#pragma unroll
+  for (int i = 0; i < kTwFetch; ++i) {
+    const int m = tid + i * nthr;
+    if (m < n) tw[m] = f.v[i];
+  }
+}
+// The whole table of length n in LDS (visible after the caller's next
+// barrier), evaluated: for kernels that cannot overlap a table copy with
+// their own loads (a copy waited on at once costs them more than the FP64
+// evaluation, e.g. the TF field pass at 384 points: 55 -> 58 us).
+__device__ __forceinline__ void fill_twiddles(float2* tw, int n, int tid, int nthr) {
+  compute_twiddles(tw, n, tid, nthr);
 }
 
 // Cooperative copy of `total` (<= kEmax * nthr) elements into LDS, element e
@@ -798,12 +945,26 @@ namespace wo {
 // and shifts.  Used for the transform lengths of the workloads; other lengths
 // take the runtime plan above.
 
-template <int N>
+template <int N, bool W16 = false>
 struct StaticPlan {
   // radices in the order 8, 4, 6, 2, 3, 5: a radix-6 butterfly (two radix-3
   // DFTs in registers) replaces a radix-2 and a radix-3 pass, one LDS round
   // trip fewer (384 = 8 8 6, 240 = 8 6 5, 48 = 8 6)
+  // W16, for 2^t with t = 3a + 1 >= 7 (128, 1024): 8 ... 8 then 16, one LDS
+  // round trip fewer than 8 ... 8 then 2, for kernels with the registers for
+  // a 16-point butterfly (about 20 more VGPRs)
+  static constexpr bool last16() {
+    int t = 0;
+    while ((1 << t) < N) ++t;
+    return W16 && (1 << t) == N && t >= 7 && t % 3 == 1;
+  }
   static constexpr int radix(int q) {
+    if (last16()) {
+      int t = 0;
+      while ((1 << t) < N) ++t;
+      const int np = (t - 4) / 3 + 1;
+      return q < np - 1 ? 8 : (q == np - 1 ? 16 : 0);
+    }
     int m = N, p = 0;
     const int order[6] = {8, 4, 6, 2, 3, 5};
     for (int i = 0; i < 6; ++i) {
@@ -901,10 +1062,10 @@ __device__ __forceinline__ void static_fft(float2* lds, int nl_rt, int es, int l
 // radices before it); a transform in reversed order ends with a pass whose
 // outputs, k + r N/R0, are the inputs of the first pass (radix R0, span 1) of
 // a transform in forward order, so the two can meet in registers.
-template <int N, bool REV>
+template <int N, bool REV, bool W16 = false>
 struct OrderedPlan {
-  static constexpr int passes() { return StaticPlan<N>::passes(); }
-  static constexpr int radix(int q) { return StaticPlan<N>::radix(REV ? passes() - 1 - q : q); }
+  static constexpr int passes() { return StaticPlan<N, W16>::passes(); }
+  static constexpr int radix(int q) { return StaticPlan<N, W16>::radix(REV ? passes() - 1 - q : q); }
   static constexpr int span(int q) {
     int s = 1;
     for (int i = 0; i < q; ++i) s *= radix(i);
@@ -913,14 +1074,14 @@ struct OrderedPlan {
 };
 
 // Passes [Q, QE) of the compiled transform of length N in the given order.
-template <int N, int NL, bool LF, int EM, bool PD, bool REV, int Q, int QE>
+template <int N, int NL, bool LF, int EM, bool PD, bool REV, int Q, int QE, bool W16 = false>
 __device__ __forceinline__ void static_passes(float2* lds, int nl_rt, int es, int ls, int shift,
                                               const float2* tw, float s, int tid, int nthr) {
   if constexpr (Q < QE) {
-    using PL = OrderedPlan<N, REV>;
+    using PL = OrderedPlan<N, REV, W16>;
     static_pass<N, PL::radix(Q), PL::span(Q), NL, LF, EM, PD>(lds, nl_rt, es, ls, shift, tw, s, tid,
                                                              nthr);
-    static_passes<N, NL, LF, EM, PD, REV, Q + 1, QE>(lds, nl_rt, es, ls, shift, tw, s, tid, nthr);
+    static_passes<N, NL, LF, EM, PD, REV, Q + 1, QE, W16>(lds, nl_rt, es, ls, shift, tw, s, tid, nthr);
   }
 }
 
@@ -1027,17 +1188,23 @@ __device__ __forceinline__ void first_pass_in(float2* lds, int nl_rt, int es, in
                                          [](int, int, float2 v) { return v; }, mid);
 }
 
-template <int N, int NL, bool LF, int EM, bool PD, bool REV, typename ST>
+template <int N, int NL, bool LF, int EM, bool PD, bool REV, bool W16 = false, typename ST>
 __device__ __forceinline__ void last_pass_out(const float2* lds, int nl_rt, int es, int ls, int shift,
                                               const float2* tw, float s, int tid, int nthr, ST store) {
-  using PL = OrderedPlan<N, REV>;
+  using PL = OrderedPlan<N, REV, W16>;
   constexpr int NP = PL::passes();
   constexpr int RL = PL::radix(NP - 1), NSL = N / RL;
   constexpr int BL = (EM + RL - 1) / RL;
   const int nl = NL > 0 ? NL : nl_rt;
+  // every butterfly of the thread first, then the stores: a register that a
+  // store reads is not reused by the next butterfly, which would make the
+  // compiler wait for the stores to complete (vmcnt) between butterflies
+  float2 x[BL][RL];
+  int ll[BL], kk[BL];
 #pragma unroll
   for (int b = 0; b < BL; ++b) {
     const int j = tid + b * nthr;
+    kk[b] = -1;
     if (j < nl * NSL) {
       int l, k;
       line_of<N, NL, LF, PD>(j, nl, NSL, shift, l, k);
@@ -1045,16 +1212,22 @@ __device__ __forceinline__ void last_pass_out(const float2* lds, int nl_rt, int 
       float2 w1 = tw[k];   // span NSL = N / RL: twiddle stride 1
       if (s > 0.f) w1.y = -w1.y;
       twiddle_powers<RL>(w, w1);
-      float2 x[RL];
 #pragma unroll
       for (int r = 0; r < RL; ++r) {
         const int i = k + r * NSL;
-        x[r] = lds[l * ls + (PD ? row_slot(i, pad_shift(N)) : i * es)];
-        if (r > 0) x[r] = cmul(x[r], w[r]);
+        x[b][r] = lds[l * ls + (PD ? row_slot(i, pad_shift(N)) : i * es)];
+        if (r > 0) x[b][r] = cmul(x[b][r], w[r]);
       }
-      dft_small<RL>(x, s);
+      dft_small<RL>(x[b], s);
+      ll[b] = l;
+      kk[b] = k;
+    }
+  }
 #pragma unroll
-      for (int r = 0; r < RL; ++r) store(l, k + r * NSL, x[r]);
+  for (int b = 0; b < BL; ++b) {
+    if (kk[b] >= 0) {
+#pragma unroll
+      for (int r = 0; r < RL; ++r) store(ll[b], kk[b] + r * NSL, x[b][r]);
     }
   }
   __syncthreads();

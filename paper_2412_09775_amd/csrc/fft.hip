@@ -48,16 +48,20 @@ __global__ __launch_bounds__(1024) void k_rows_r2c(const float* __restrict__ in,
     return make_float2(in[ra + i], in[(rb >= 0 ? rb : ra) + i]);
   };
   auto finish = [&](int l, int, float2 v) { return make_float2(v.x, rin[2 * l + 1] >= 0 ? v.y : 0.f); };
-  // twiddles before the loads: few threads evaluate them (symmetric fill), and
-  // nothing of it stays live while the loads are in flight
-  fill_twiddles(tw, Xc, tid, nthr);
+  // the twiddle-table loads are issued first and written to LDS once the data
+  // loads are in flight
+  TwFetch twf;
+  tw_begin(twf, tw, Xc, tid, nthr);
   if constexpr (NS > 0) {
-    // first pass straight from memory
+    // first pass straight from memory; radices 8 ... 8 16 where that saves a
+    // pass (the first radix is the same)
+    static_assert(OrderedPlan<NS, false, true>::radix(0) == OrderedPlan<NS, false>::radix(0), "first pass");
     first_pass_in2<NS, 0, false, kEmax, true, false>(buf, nl, 1, LS, -1, -1.f, tid, nthr, load, finish,
-                                                     [] {});
-    static_passes<NS, 0, false, kEmax, true, false, 1, StaticPlan<NS>::passes()>(buf, nl, 1, LS, -1, tw,
-                                                                                -1.f, tid, nthr);
+                                                     [&] { tw_end(twf, tw, Xc, tid, nthr); });
+    static_passes<NS, 0, false, kEmax, true, false, 1, StaticPlan<NS, true>::passes(), true>(
+        buf, nl, 1, LS, -1, tw, -1.f, tid, nthr);
   } else {
+    tw_end(twf, tw, Xc, tid, nthr);
     gather2_to_lds(buf, nl * Xc, tid, nthr, [&](int e) {
       const int l = e / Xc;
       return load(l, e - l * Xc);
@@ -141,15 +145,19 @@ __global__ __launch_bounds__(1024) void k_rows_c2r(const float2* __restrict__ in
     __builtin_nontemporal_store(v.x * scale, &out[rout[2 * l] + i]);
     if (rout[2 * l + 1] >= 0) __builtin_nontemporal_store(v.y * scale, &out[rout[2 * l + 1] + i]);
   };
-  fill_twiddles(tw, Xc, tid, nthr);   // before the loads, as in k_rows_r2c
+  TwFetch twf;   // as in k_rows_r2c
+  tw_begin(twf, tw, Xc, tid, nthr);
   if constexpr (NS > 0) {
-    // first pass straight from memory, last pass straight to memory
+    // first pass straight from memory, last pass straight to memory (the
+    // 8 ... 8 16 plan of k_rows_r2c is slower here: its 16-point last pass
+    // stores from half the threads, 320 -> 339 us on 4 x 64 x 1024 rows of 1024)
     constexpr int NP = StaticPlan<NS>::passes();
     first_pass_in2<NS, 0, false, kEmax, true, false>(buf, nl, 1, LS, -1, 1.f, tid, nthr, load, finish,
-                                                     [] {});
+                                                     [&] { tw_end(twf, tw, Xc, tid, nthr); });
     static_passes<NS, 0, false, kEmax, true, false, 1, NP - 1>(buf, nl, 1, LS, -1, tw, 1.f, tid, nthr);
     last_pass_out<NS, 0, false, kEmax, true, false>(buf, nl, 1, LS, -1, tw, 1.f, tid, nthr, store);
   } else {
+    tw_end(twf, tw, Xc, tid, nthr);
     gather2_to_lds(buf, nl * Xc, tid, nthr, [&](int e) {
       const int l = e / Xc;
       return load(l, e - l * Xc);
@@ -312,18 +320,20 @@ __global__ __launch_bounds__(1024, 8) void k_cols(float2* __restrict__ data, int
   const int Nc = NS > 0 ? NS : N;
   auto ld_ok = [&](int l, int n) { return l < weff && (band != 2 || in_band(n, ky, nb, Nc)); };
   auto st_ok = [&](int l, int n) { return l < weff && (band != 1 || in_band(n, ky, nb, Nc)); };
-  fill_twiddles(tw, Nc, tid, nthr);   // before the loads, as in the row passes
+  TwFetch twf;   // as in the row passes
+  tw_begin(twf, tw, Nc, tid, nthr);
   if constexpr (NS > 0) {
     // line l = column m0 + l; first pass straight from memory, last pass
     // straight to memory
     fft_direct<NS, WS, true, kEmax, false>(
         buf, W, W, 1, wsh, tw, sign, tid, nthr,
         [&](int l, int n) { return ld_ok(l, n) ? base[(long)n * M + m0 + l] : make_float2(0.f, 0.f); },
-        [] {},
+        [&] { tw_end(twf, tw, Nc, tid, nthr); },
         [&](int l, int n, float2 v) {
           if (st_ok(l, n)) base[(long)n * M + m0 + l] = v;
         });
   } else {
+    tw_end(twf, tw, Nc, tid, nthr);
     gather_to_lds(buf, Nc * W, tid, nthr, [&](int e) {
       const int n = e >> wsh, w = e & (W - 1);
       return ld_ok(w, n) ? base[(long)n * M + m0 + w] : make_float2(0.f, 0.f);
@@ -843,7 +853,8 @@ __global__ __launch_bounds__(1024, NS > 0 ? 7 : 1) void k_zop(float2* __restrict
       }
     }
   }
-  fill_twiddles(tw, Zc, tid, nthr);   // before the data loads, as in the row passes
+  TwFetch twf;   // as in the row passes
+  tw_begin(twf, tw, Zc, tid, nthr);
   // LDS holds [z][ch][w]: line l = ch W + w, element z at z CH W
   if constexpr (NS > 0) {
     // first pass of the forward Z transform straight from memory
@@ -853,10 +864,11 @@ __global__ __launch_bounds__(1024, NS > 0 ? 7 : 1) void k_zop(float2* __restrict
           const int ch = l >> wsh, w = l & (W - 1);
           return w < weff ? st[soff(ch * Zc + z) + w] : make_float2(0.f, 0.f);
         },
-        [] {});
+        [&] { tw_end(twf, tw, Zc, tid, nthr); });
     static_passes<NS, 0, true, kEmax, false, false, 1, StaticPlan<NS>::passes()>(
         buf, cin * W, CH * W, 1, pow2_shift(cin * W), tw, -1.f, tid, nthr);
   } else {
+    tw_end(twf, tw, Zc, tid, nthr);
     // element e = (ch, z, w) of the global tile goes to LDS [z][ch][w]
     float2 t[kEmax];
 #pragma unroll
